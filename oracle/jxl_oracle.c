@@ -1,0 +1,1031 @@
+/*
+ * jxl_oracle.c -- plain FP64 CPU oracle for JPEG XL VarDCT pixel reconstruction.
+ *
+ * TEST INFRASTRUCTURE ONLY: see jxl_oracle.h.  Written from the JPEG XL
+ * Committee Draft (ISO/IEC 18181 CD, 2019-08-05).  Each function is the
+ * draft's definition written out in the draft's order, with no blocking,
+ * fusion or reordering; loops are plain and slow on purpose.  Where the draft
+ * is silent, garbled or inconsistent, the reading taken is stated at the spot
+ * and listed in the design notes of the repository.
+ *
+ * Parity status per function (pins live in tests/test_oracle_pins.py):
+ *   transform matrices, inverse/forward transforms, LLF<->DC   pinned
+ *   dequantization matrices                                     partially pinned
+ *       (positivity, symmetry and closed-form band values only; the numerator
+ *        reading of C.6.1 cannot be checked against anything but itself)
+ *   reconstruct, gaborish, xyb_to_rgb, quantize_srgb            pinned
+ *   edge-preserving filter                                      pinned by
+ *       invariants and a step-edge closed form
+ */
+#include "jxl_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define PI 3.14159265358979323846
+
+/* ======================================================================= */
+/* Defaults (C.4.1-C.4.3, C.10, L.2, A.4.5)                                */
+/* ======================================================================= */
+
+void orc_params_default(orc_params* p, int32_t xsize, int32_t ysize) {
+  memset(p, 0, sizeof(*p));
+  p->xsize = xsize;
+  p->ysize = ysize;
+  /* C.4.2 has no default; 1 is the smallest value the U32 can code. */
+  p->global_scale = 1;
+  /* C.4.1: weights {4096, 512, 256} times 1 / (global_scale * quant_dc),
+   * here with global_scale = 1 and quant_dc = 1. */
+  p->dc_mul[0] = 4096.0;
+  p->dc_mul[1] = 512.0;
+  p->dc_mul[2] = 256.0;
+  /* C.4.3 + Annex G: x_factor_dc = b_factor_dc = 128. */
+  p->kx_dc = (128.0 - 128.0) / 256.0;
+  p->kb_dc = 0.935669 + (128.0 - 128.0) / 128.0;
+  /* C.10 LoopFilter defaults. */
+  p->gab = 1;
+  for (int c = 0; c < 3; ++c) {
+    p->gab_w1[c] = 0.115169525;
+    p->gab_w2[c] = 0.061248592;
+  }
+  p->epf_iters = 1;
+  p->epf_weight_min = 0.3;
+  p->epf_scale[0] = 899.676941;
+  p->epf_scale[1] = 111.965157;
+  p->epf_scale[2] = 45.275791;
+  for (int i = 0; i < 8; ++i) p->epf_sharp_lut[i] = i / 7.0;
+  p->epf_range_max = 70.0;
+  p->epf_range_mul = 12.6;
+  p->epf_quant_mul = 20.0;
+  p->epf_sigma_max = 170;
+  p->epf_sigma_shift = 0;
+  /* L.2 default inverse opsin absorbance matrix and biases. */
+  static const double m[9] = {
+      2542.56835937500000, -2326.53173828125000, 44.17734527587891,
+      -698.04852294921875, 1012.71777343750000, -76.22974395751953,
+      -827.36480712890625, 709.83502197265625,  451.38488769531250};
+  memcpy(p->opsin_inv, m, sizeof(m));
+  p->opsin_bias[0] = -0.00100549;
+  p->opsin_bias[1] = -0.00100549;
+  p->opsin_bias[2] = -0.00094081;
+  p->target_nits_div50 = 5;  /* A.4.5 */
+}
+
+int orc_num_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
+/* ======================================================================= */
+/* Varblock geometry (C.5.4 table, I.2.5)                                  */
+/* ======================================================================= */
+
+/* I.2.5: "DCT N x M" has bxsize = max(8, N) and bysize = max(8, M); every other
+ * transform covers 8 x 8.  The first number is read as the width. */
+int orc_varblock_size(int s, int32_t* bx, int32_t* by) {
+  static const int32_t w[15] = {8, 8, 8, 8, 16, 32, 16, 8, 32, 8, 32, 16, 8, 8, 8};
+  static const int32_t h[15] = {8, 8, 8, 8, 16, 32, 8, 16, 8, 32, 16, 32, 8, 8, 8};
+  if (s < 0 || s > 14) return 0;
+  *bx = w[s];
+  *by = h[s];
+  return 1;
+}
+
+/* Transform types this oracle reconstructs (DCT4x8, DCT8x4 and AFV are not). */
+static int supported(int s) { return s >= 0 && s <= 11; }
+
+static int is_dct_family(int s) {
+  return s == ORC_DCT8 || (s >= ORC_DCT16 && s <= ORC_DCT16X32);
+}
+
+/* ======================================================================= */
+/* One-dimensional transforms (I.2.1 and the Annex R generator)            */
+/* ======================================================================= */
+
+/* The inverse transform of I.2.1 is the DCT-III with column k scaled:
+ *   out[n] = sum_k s_N(k) * cos(pi * (2n + 1) * k / (2N)) * in[k],
+ * s_N(0) = 1; s_8(k) = 1 / cos(k pi / 16) for the 8-point butterfly;
+ * s_N(k) = 2 cos(k pi / (2N)) for the generated 2-, 4-, 16- and 32-point
+ * transforms.  The forward transform is N times its inverse matrix:
+ *   out[k] = r_N(k) * sum_n cos(pi * (2n + 1) * k / (2N)) * in[n],
+ * r_N(0) = 1 and r_N(k) = 2 / s_N(k).  The tests pin both closed forms
+ * against the butterfly and the generator's recursion. */
+static double col_scale(int32_t N, int32_t k) {
+  if (k == 0) return 1.0;
+  if (N == 8) return 1.0 / cos(k * PI / 16.0);
+  return 2.0 * cos(k * PI / (2.0 * N));
+}
+
+static int valid_n(int32_t N) {
+  return N == 1 || N == 2 || N == 4 || N == 8 || N == 16 || N == 32;
+}
+
+int orc_idct_matrix(int32_t N, double* out) {
+  if (!valid_n(N)) return ORC_E_PARAM;
+  for (int32_t n = 0; n < N; ++n)
+    for (int32_t k = 0; k < N; ++k)
+      out[n * N + k] = col_scale(N, k) * cos(PI * (2 * n + 1) * k / (2.0 * N));
+  return ORC_OK;
+}
+
+int orc_fdct_matrix(int32_t N, double* out) {
+  if (!valid_n(N)) return ORC_E_PARAM;
+  for (int32_t k = 0; k < N; ++k)
+    for (int32_t n = 0; n < N; ++n) {
+      double r = (k == 0) ? 1.0 : 2.0 / col_scale(N, k);
+      out[k * N + n] = r * cos(PI * (2 * n + 1) * k / (2.0 * N));
+    }
+  return ORC_OK;
+}
+
+/* ======================================================================= */
+/* Scale factors (I.2.6.1)                                                 */
+/* ======================================================================= */
+
+static double I8f(int32_t N, int32_t u) {
+  double eps = (u == 0) ? sqrt(0.5) : 1.0;
+  return sqrt(2.0 / N) * eps * cos(u * PI / (2.0 * N));
+}
+static double D8f(int32_t N, int32_t u) { return 1.0 / (N * I8f(N, u)); }
+
+double orc_scale_I(int32_t N, int32_t u) { return N == 8 ? I8f(N, u) : D8f(N, u); }
+double orc_scale_D(int32_t N, int32_t u) { return N == 8 ? D8f(N, u) : I8f(N, u); }
+
+static double Cf(int32_t N, int32_t n, int32_t x) {
+  if (n > N) return 1.0 / Cf(n, N, x);
+  if (n == N) return 1.0;
+  return cos(x * PI / (2.0 * N)) * Cf(N / 2, n, x);
+}
+
+double orc_scalef(int32_t N, int32_t n, int32_t x) {
+  return sqrt((double)n * N) * orc_scale_D(N, x) * orc_scale_I(n, x) * Cf(N, n, x);
+}
+
+/* ======================================================================= */
+/* Two-dimensional transforms (I.2.2, I.2.3, I.2.4)                        */
+/* ======================================================================= */
+
+/* Arrays are [rows][cols] = [y][x]; entry (x, y) of the draft is a[y * cols + x].
+ *
+ * Reading of I.2.2: coefficient (x, y) carries horizontal frequency x and
+ * vertical frequency y for every size, so the 2-D inverse is
+ * S = T_by * K * T_bx^T (rows transformed by T_by, columns by T_bx); the
+ * draft's square form, which omits the final transpose, differs only by this
+ * relabelling of a square coefficient array. */
+static void idct_2d(int32_t bx, int32_t by, const double* K, double* S) {
+  double Tx[32 * 32], Ty[32 * 32], tmp[32 * 32];
+  orc_idct_matrix(bx, Tx);
+  orc_idct_matrix(by, Ty);
+  /* Column pass: tmp = T_by * K. */
+  for (int32_t n = 0; n < by; ++n)
+    for (int32_t x = 0; x < bx; ++x) {
+      double acc = 0.0;
+      for (int32_t k = 0; k < by; ++k) acc += Ty[n * by + k] * K[k * bx + x];
+      tmp[n * bx + x] = acc;
+    }
+  /* Row pass: S = tmp * T_bx^T. */
+  for (int32_t n = 0; n < by; ++n)
+    for (int32_t m = 0; m < bx; ++m) {
+      double acc = 0.0;
+      for (int32_t k = 0; k < bx; ++k) acc += tmp[n * bx + k] * Tx[m * bx + k];
+      S[n * bx + m] = acc;
+    }
+}
+
+static void fdct_2d(int32_t bx, int32_t by, const double* S, double* K) {
+  double Fx[32 * 32], Fy[32 * 32], tmp[32 * 32];
+  orc_fdct_matrix(bx, Fx);
+  orc_fdct_matrix(by, Fy);
+  for (int32_t k = 0; k < by; ++k)
+    for (int32_t x = 0; x < bx; ++x) {
+      double acc = 0.0;
+      for (int32_t n = 0; n < by; ++n) acc += Fy[k * by + n] * S[n * bx + x];
+      tmp[k * bx + x] = acc;
+    }
+  for (int32_t k = 0; k < by; ++k)
+    for (int32_t l = 0; l < bx; ++l) {
+      double acc = 0.0;
+      for (int32_t m = 0; m < bx; ++m) acc += tmp[k * bx + m] * Fx[l * bx + m];
+      K[k * bx + l] = acc;
+    }
+}
+
+/* AuxIDCT2x2(block, S) of I.2.4.2 on an 8 x 8 array: the top S x S cells are
+ * replaced, the rest copied. */
+static void aux_idct2x2(const double* blk, int S, double* res) {
+  memcpy(res, blk, 64 * sizeof(double));
+  int h = S / 2;
+  for (int y = 0; y < h; ++y)
+    for (int x = 0; x < h; ++x) {
+      double c00 = blk[y * 8 + x];
+      double c01 = blk[y * 8 + h + x];
+      double c10 = blk[(h + y) * 8 + x];
+      double c11 = blk[(h + y) * 8 + h + x];
+      res[(2 * y) * 8 + 2 * x] = c00 + c01 + c10 + c11;
+      res[(2 * y) * 8 + 2 * x + 1] = c00 + c01 - c10 - c11;
+      res[(2 * y + 1) * 8 + 2 * x] = c00 - c01 + c10 - c11;
+      res[(2 * y + 1) * 8 + 2 * x + 1] = c00 - c01 - c10 + c11;
+    }
+}
+
+/* AuxDCT2x2(block, S) of I.2.3.2. */
+static void aux_dct2x2(const double* blk, int S, double* res) {
+  memcpy(res, blk, 64 * sizeof(double));
+  int h = S / 2;
+  for (int y = 0; y < h; ++y)
+    for (int x = 0; x < h; ++x) {
+      double c00 = blk[(2 * y) * 8 + 2 * x];
+      double c01 = blk[(2 * y) * 8 + 2 * x + 1];
+      double c10 = blk[(2 * y + 1) * 8 + 2 * x];
+      double c11 = blk[(2 * y + 1) * 8 + 2 * x + 1];
+      res[y * 8 + x] = (c00 + c01 + c10 + c11) / 4.0;
+      res[y * 8 + h + x] = (c00 + c01 - c10 - c11) / 4.0;
+      res[(h + y) * 8 + x] = (c00 - c01 + c10 - c11) / 4.0;
+      res[(h + y) * 8 + h + x] = (c00 - c01 - c10 + c11) / 4.0;
+    }
+}
+
+/* I.2.4.2: IDCT 2 x 2. */
+static void inv_dct2(const double* K, double* S) {
+  double a[64], b[64];
+  aux_idct2x2(K, 2, a);
+  aux_idct2x2(a, 4, b);
+  aux_idct2x2(b, 8, S);
+}
+
+/* I.2.4.3: IDCT 4 x 4. */
+static void inv_dct4(const double* K, double* S) {
+  double dcs[64];
+  aux_idct2x2(K, 2, dcs);
+  for (int sy = 0; sy < 2; ++sy)
+    for (int sx = 0; sx < 2; ++sx) {
+      double blk[16], out[16];
+      for (int iy = 0; iy < 4; ++iy)
+        for (int ix = 0; ix < 4; ++ix)
+          blk[iy * 4 + ix] = K[(sy + 2 * iy) * 8 + sx + 2 * ix];
+      blk[0] = dcs[sy * 8 + sx];
+      idct_2d(4, 4, blk, out);
+      for (int l = 0; l < 4; ++l)
+        for (int k = 0; k < 4; ++k) S[(4 * sy + l) * 8 + 4 * sx + k] = out[l * 4 + k];
+    }
+}
+
+/* I.2.4.4: Identity. */
+static void inv_identity(const double* K, double* S) {
+  double dcs[64];
+  aux_idct2x2(K, 2, dcs);
+  for (int sy = 0; sy < 2; ++sy)
+    for (int sx = 0; sx < 2; ++sx) {
+      double block_dc = dcs[sy * 8 + sx];
+      double residual_sum = 0.0;
+      for (int iy = 0; iy < 4; ++iy)
+        for (int ix = 0; ix < 4; ++ix) {
+          if (ix == 0 && iy == 0) continue;
+          residual_sum += K[(sy + 2 * iy) * 8 + sx + 2 * ix];
+        }
+      double s11 = block_dc - residual_sum / 16.0;
+      S[(4 * sy + 1) * 8 + 4 * sx + 1] = s11;
+      for (int iy = 0; iy < 4; ++iy)
+        for (int ix = 0; ix < 4; ++ix) {
+          if (ix == 1 && iy == 1) continue;
+          S[(4 * sy + iy) * 8 + 4 * sx + ix] = K[(sy + 2 * iy) * 8 + sx + 2 * ix] + s11;
+        }
+      S[(4 * sy) * 8 + 4 * sx] = K[(sy + 2) * 8 + sx + 2] + s11;
+    }
+}
+
+int orc_inverse_transform(int s, const double* K, double* S) {
+  int32_t bx, by;
+  if (!supported(s) || !orc_varblock_size(s, &bx, &by)) return ORC_E_STRATEGY;
+  if (s == ORC_DCT2) inv_dct2(K, S);
+  else if (s == ORC_DCT4) inv_dct4(K, S);
+  else if (s == ORC_IDENTITY) inv_identity(K, S);
+  else idct_2d(bx, by, K, S);
+  return ORC_OK;
+}
+
+/* I.2.3.2: DCT 2 x 2. */
+static void fwd_dct2(const double* S, double* K) {
+  double a[64], b[64];
+  aux_dct2x2(S, 8, a);
+  aux_dct2x2(a, 4, b);
+  aux_dct2x2(b, 2, K);
+}
+
+/* I.2.3.3: DCT 4 x 4. */
+static void fwd_dct4(const double* S, double* K) {
+  double tmp[64];
+  for (int sy = 0; sy < 2; ++sy)
+    for (int sx = 0; sx < 2; ++sx) {
+      double blk[16], c[16];
+      for (int l = 0; l < 4; ++l)
+        for (int k = 0; k < 4; ++k) blk[l * 4 + k] = S[(4 * sy + l) * 8 + 4 * sx + k];
+      fdct_2d(4, 4, blk, c);
+      for (int iy = 0; iy < 4; ++iy)
+        for (int ix = 0; ix < 4; ++ix) tmp[(sy + 2 * iy) * 8 + sx + 2 * ix] = c[iy * 4 + ix];
+    }
+  aux_dct2x2(tmp, 2, K);
+}
+
+/* I.2.3.4: Identity. */
+static void fwd_identity(const double* S, double* K) {
+  double tmp[64];
+  for (int sy = 0; sy < 2; ++sy)
+    for (int sx = 0; sx < 2; ++sx) {
+      double block_dc = 0.0;
+      for (int iy = 0; iy < 4; ++iy)
+        for (int ix = 0; ix < 4; ++ix) block_dc += S[(4 * sy + iy) * 8 + 4 * sx + ix];
+      block_dc /= 16.0;
+      double s11 = S[(4 * sy + 1) * 8 + 4 * sx + 1];
+      for (int iy = 0; iy < 4; ++iy)
+        for (int ix = 0; ix < 4; ++ix) {
+          if (ix == 1 && iy == 1) continue;
+          tmp[(sy + 2 * iy) * 8 + sx + 2 * ix] = S[(4 * sy + iy) * 8 + 4 * sx + ix] - s11;
+        }
+      tmp[(sy + 2) * 8 + sx + 2] = tmp[sy * 8 + sx];
+      tmp[sy * 8 + sx] = block_dc;
+    }
+  aux_dct2x2(tmp, 2, K);
+}
+
+int orc_forward_transform(int s, const double* S, double* K) {
+  int32_t bx, by;
+  if (!supported(s) || !orc_varblock_size(s, &bx, &by)) return ORC_E_STRATEGY;
+  if (s == ORC_DCT2) fwd_dct2(S, K);
+  else if (s == ORC_DCT4) fwd_dct4(S, K);
+  else if (s == ORC_IDENTITY) fwd_identity(S, K);
+  else fdct_2d(bx, by, S, K);
+  return ORC_OK;
+}
+
+/* ======================================================================= */
+/* LLF <-> downsampled image (I.2.6, I.2.7), N = 8                         */
+/* ======================================================================= */
+
+/* I.2.7.2 for the DCT family: C = DCT_2D(dc) (cy x cx), then
+ * llf(x, y) = C(x, y) * ScaleF(cy, bysize, y) * ScaleF(cx, bxsize, x) / (cx * cy).
+ * Reading: the division by cx * cy is not printed; without it I.2.7 would be
+ * cx * cy times the inverse of I.2.6, which the draft says it is.
+ * I.2.7.3 (N = 8) for the 8 x 8 transforms: llf = dc. */
+int orc_llf_from_dc(int s, const double* dc, double* llf) {
+  int32_t bx, by;
+  if (!supported(s) || !orc_varblock_size(s, &bx, &by)) return ORC_E_STRATEGY;
+  int32_t cx = bx / 8, cy = by / 8;
+  if (!is_dct_family(s) || (cx == 1 && cy == 1)) {
+    llf[0] = dc[0];
+    return ORC_OK;
+  }
+  double C[16];
+  fdct_2d(cx, cy, dc, C);
+  for (int32_t y = 0; y < cy; ++y)
+    for (int32_t x = 0; x < cx; ++x)
+      llf[y * cx + x] = C[y * cx + x] * orc_scalef(cy, by, y) * orc_scalef(cx, bx, x) /
+                        (double)(cx * cy);
+  return ORC_OK;
+}
+
+/* I.2.6.2 (N = 8): scale the top cx x cy coefficients by
+ * ScaleF(bysize, cy, y) * ScaleF(bxsize, cx, x) and take their cy x cx IDCT_2D.
+ * I.2.6.3 for the 8 x 8 transforms: the single output is input(0, 0). */
+int orc_dc_from_llf(int s, const double* llf, double* dc) {
+  int32_t bx, by;
+  if (!supported(s) || !orc_varblock_size(s, &bx, &by)) return ORC_E_STRATEGY;
+  int32_t cx = bx / 8, cy = by / 8;
+  if (!is_dct_family(s) || (cx == 1 && cy == 1)) {
+    dc[0] = llf[0];
+    return ORC_OK;
+  }
+  double L[16];
+  for (int32_t y = 0; y < cy; ++y)
+    for (int32_t x = 0; x < cx; ++x)
+      L[y * cx + x] = llf[y * cx + x] * orc_scalef(by, cy, y) * orc_scalef(bx, cx, x);
+  idct_2d(cx, cy, L, dc);
+  return ORC_OK;
+}
+
+/* ======================================================================= */
+/* Dequantization matrices (C.6.1, defaults C.6.1.1)                       */
+/* ======================================================================= */
+
+/* Default distance and eccentricity bands of the DCT-mode encodings (C.6.1.1),
+ * per channel X, Y, B. */
+static const double DB_DCT8[3][6] = {{5.0, 0.0, -0.4, -0.4, -0.4, -2.0},
+                                     {1.1, 0.0, -0.3, -0.3, -0.3, -0.3},
+                                     {1.0, -3.0, 0.0, 0.0, -1.0, -2.0}};
+static const double DB_DCT4[3][4] = {{32.0, -0.4, 0.0, 0.0},
+                                     {6.0, 0.0, 0.0, -0.0},
+                                     {4.0, -5.0, -1.0, -1.0}};
+static const double P_DCT4[3][2] = {{1.0, 1.0}, {0.7, 0.7}, {1.0, 1.0}};
+static const double DB_DCT16[3][7] = {
+    {3.1965020925735868, -1.8000777393353804, -0.39424529824571225, -0.33909377445710343,
+     -0.6350101832695744, -0.90177264050827612, -1.5162099239887414},
+    {0.77917081615440487, -0.57424582104194355, -0.90745813428471001, -0.64925837484843441,
+     -0.35865440981033403, -0.21322389111877305, -0.27615025315725483},
+    {0.22259376988644336, -3.0531423165804414, -0.2, -0.30687130033378396,
+     -0.42708730624733904, -1.4856834539296244, -5.9209142884401604}};
+static const double DB_DCT32[3][8] = {
+    {0.47968775359573942, -1.025, -0.98, -0.9012, -0.4, -0.48819395464, -0.421064, -0.27},
+    {0.22295421389982905, -0.8041958212306401, -0.7633036457487539, -0.55660379990111464,
+     -0.49785304658857626, -0.43699592683512467, -0.40180866526242109, -0.27321683125358037},
+    {0.11607457694128877, -3.060733579805728, -2.0413270132490346, -2.0235650159727417,
+     -0.5495389509954993, -0.4, -0.4, -0.3}};
+static const double DB_DCT16X8[3][7] = {{5.0, -0.7, -0.7, -0.2, -0.2, -0.2, -0.5},
+                                        {1.0, -0.5, -0.5, -0.5, -0.2, -0.2, -0.2},
+                                        {0.35, -1.4, -0.2, -0.5, -0.5, -1.5, -3.6}};
+static const double DB_DCT32X8[3][8] = {
+    {0.90897201669289496, -2.523575079652864, 1.5606102630460328, -0.6828050717528521,
+     -14.770016895841904, -31.365240527393656, 0.565929254166433, 26.789646874558219},
+    {0.3603042187746216, -0.11724474917749789, -0.85426302204085935, -0.5404181207241352,
+     -0.45637619443533173, -0.82707923060149569, -1.09760551067614, -54.16057009483842},
+    {0.25176400522276937, -10.060949304689093, -4.5316627381323995, -5.4569229849460807,
+     -10.549754675878864, 1.7512906265092971, -1.6854706115725824, 3.3092762331901451}};
+static const double EB_DCT32X8[3][4] = {
+    {-0.40751133465833289, 2.2055690721475925, -1.4434547377534228, 2.0590289434445102},
+    {0.12452072219659419, 0.065578935001406033, -0.14598888885596958, 0.12114139909222557},
+    {0.0586589025020419, -2.2654958780302183, -4.6996221931893647, 1.8254498073137184}};
+static const double DB_DCT32X16[3][8] = {
+    {1.1280371559733287, -0.98868, -0.658, -0.42026, -0.22712, -0.2206, -0.226, -0.2},
+    {0.38961075971152237, -0.62525308982767058, -0.83770786552491361, -0.79014862079498627,
+     -0.2692727459704829, -0.38272769465388551, -0.2292422253091453, -0.20719098826199578},
+    {0.098, -2.41, -0.23, -0.2, -0.4, -0.8, -0.4, -0.5}};
+static const double P_IDENTITY[3][3] = {
+    {221.50801256717435, 7087.151589594002, 4466.9924939259863},
+    {29.535505378287006, 1454.6663024982124, 1368.041230099175},
+    {9.2887405354132238, 23.982311358829531, 11.201853748207084}};
+static const double P_DCT2[3][6] = {{3840.0, 2560.0, 1280.0, 640.0, 480.0, 300.0},
+                                    {960.0, 640.0, 320.0, 180.0, 140.0, 120.0},
+                                    {640.0, 320.0, 128.0, 64.0, 32.0, 16.0}};
+
+static double band_factor(double v) { return v > 0 ? (v + 1.0) : (1.0 / (1.0 - v)); }
+
+/* interpolate() of C.6.1.  Reading: when the scaled position reaches the last
+ * band (eccentricity 1 on the axes), the last band value is returned instead
+ * of reading past the array. */
+static double interpolate(double pos, double maxv, const double* bands, int len) {
+  double scaled_pos = pos * (len - 1) / maxv;
+  int idx = (int)floor(scaled_pos);
+  if (idx >= len - 1) return bands[len - 1];
+  double frac = scaled_pos - idx;
+  double A = bands[idx], B = bands[idx + 1];
+  return A * pow(B / A, frac);
+}
+
+/* Weights of the DCT encoding mode for an X-column by Y-row matrix.
+ * Reading of the distance-band recurrence: bands[0] = db[0] and
+ * bands[i] = bands[i - 1] * factor(db[i]) for 1 <= i < num_bands (the printed
+ * loop writes index i + 1 and would leave index 1 unset). */
+static void dct_weights(int X, int Y, const double* db, int nb, const double* eb, int ne,
+                        double* w) {
+  double dbands[16], ebands[16];
+  dbands[0] = db[0];
+  for (int i = 1; i < nb; ++i) dbands[i] = dbands[i - 1] * band_factor(db[i]);
+  ebands[0] = 1.0;
+  for (int i = 0; i < ne; ++i) ebands[i + 1] = ebands[i] * band_factor(eb ? eb[i] : 0.0);
+  for (int y = 0; y < Y; ++y)
+    for (int x = 0; x < X; ++x) {
+      double fx = (double)x / X, fy = (double)y / Y;
+      double dist = sqrt(fx * fx + fy * fy);
+      double dm = interpolate(dist, sqrt(2.0), dbands, nb);
+      /* eccentricity(0, 0) is 0 / 0; that entry is the DC slot and is never
+       * used as a multiplier, so it is given multiplier 1. */
+      double em = 1.0;
+      if (x != 0 || y != 0) em = interpolate(fabs(fx - fy) / dist, 1.0, ebands, ne + 1);
+      w[y * X + x] = dm * em;
+    }
+}
+
+int orc_dequant_matrix(int s, int c, double* out) {
+  int32_t bx, by;
+  if (!supported(s) || !orc_varblock_size(s, &bx, &by)) return ORC_E_STRATEGY;
+  if (c < 0 || c > 2) return ORC_E_PARAM;
+  double w[32 * 32], num[32 * 32];
+  int X = bx, Y = by;
+  if (s == ORC_IDENTITY) {
+    for (int i = 0; i < 64; ++i) w[i] = P_IDENTITY[c][0];
+    w[0 * 8 + 1] = w[1 * 8 + 0] = P_IDENTITY[c][1];
+    w[1 * 8 + 1] = P_IDENTITY[c][2];
+    for (int i = 0; i < 64; ++i) num[i] = 1.0;
+  } else if (s == ORC_DCT2) {
+    /* Rectangles are half-open; "and symmetric" adds the mirror image across
+     * the diagonal. */
+    for (int y = 0; y < 8; ++y)
+      for (int x = 0; x < 8; ++x) {
+        int lo = x < y ? x : y, hi = x < y ? y : x;
+        double v = 1.0;
+        if (hi == 1 && lo == 0) v = P_DCT2[c][0];
+        else if (hi == 1 && lo == 1) v = P_DCT2[c][1];
+        else if (hi >= 2 && hi < 4 && lo < 2) v = P_DCT2[c][2];
+        else if (hi >= 2 && hi < 4 && lo >= 2) v = P_DCT2[c][3];
+        else if (hi >= 4 && lo < 4) v = P_DCT2[c][4];
+        else if (hi >= 4 && lo >= 4) v = P_DCT2[c][5];
+        w[y * 8 + x] = v;
+        num[y * 8 + x] = 1.0;
+      }
+  } else if (s == ORC_DCT4) {
+    double w4[16];
+    dct_weights(4, 4, DB_DCT4[c], 4, NULL, 2, w4);
+    for (int y = 0; y < 8; ++y)
+      for (int x = 0; x < 8; ++x) w[y * 8 + x] = w4[(y / 2) * 4 + x / 2];
+    w[0 * 8 + 1] /= P_DCT4[c][0];
+    w[1 * 8 + 0] /= P_DCT4[c][0];
+    w[1 * 8 + 1] /= P_DCT4[c][1];
+    /* Numerators of a 4-point dimension use I(4, pos / 2); the division is by
+     * the matrix size X * Y = 64. */
+    for (int y = 0; y < 8; ++y)
+      for (int x = 0; x < 8; ++x)
+        num[y * 8 + x] = orc_scale_I(4, x / 2) * orc_scale_I(4, y / 2) / 64.0;
+  } else {
+    const double* db;
+    const double* eb = NULL;
+    int nb, ne;
+    switch (s) {
+      case ORC_DCT8: db = DB_DCT8[c]; nb = 6; ne = 3; break;
+      case ORC_DCT16: db = DB_DCT16[c]; nb = 7; ne = 3; break;
+      case ORC_DCT32: db = DB_DCT32[c]; nb = 8; ne = 4; break;
+      case ORC_DCT16X8: case ORC_DCT8X16: db = DB_DCT16X8[c]; nb = 7; ne = 3; break;
+      case ORC_DCT32X8: case ORC_DCT8X32:
+        db = DB_DCT32X8[c]; eb = EB_DCT32X8[c]; nb = 8; ne = 4; break;
+      default: db = DB_DCT32X16[c]; nb = 8; ne = 4; break;
+    }
+    dct_weights(X, Y, db, nb, eb, ne, w);
+    /* numerators(x, y) = I(X, x) * I(Y, y) / (X * Y). */
+    for (int y = 0; y < Y; ++y)
+      for (int x = 0; x < X; ++x)
+        num[y * X + x] = orc_scale_I(X, x) * orc_scale_I(Y, y) / (double)(X * Y);
+  }
+  for (int i = 0; i < X * Y; ++i) {
+    double v = num[i] / w[i];
+    if (i != 0 && !(v > 0.0 && isfinite(v))) return ORC_E_DEQUANT;
+    out[i] = v;
+  }
+  return ORC_OK;
+}
+
+/* ======================================================================= */
+/* Reconstruction: F.2, F.3, Annex G, I.2.7, I.2.4                         */
+/* ======================================================================= */
+
+typedef struct {
+  int32_t bx0, by0; /* top-left block */
+  int s;
+} varblock;
+
+/* Walks the DctSelect map in raster order (C.5.4): at every block not yet
+ * covered, the stored value names the varblock whose top-left it is; the
+ * varblock must be naturally aligned and inside the frame.  A varblock that
+ * would cover an already covered block is ill-formed as well. */
+static int scan_varblocks(int32_t Wb, int32_t Hb, const uint8_t* strategy, varblock* list,
+                          int32_t* count, int32_t* owner /* [Hb*Wb] or NULL */) {
+  uint8_t* covered = (uint8_t*)calloc((size_t)Wb * Hb, 1);
+  if (!covered) return ORC_E_SIZE;
+  int32_t n = 0;
+  for (int32_t by = 0; by < Hb; ++by)
+    for (int32_t bx = 0; bx < Wb; ++bx) {
+      if (covered[by * Wb + bx]) continue;
+      int s = strategy[by * Wb + bx];
+      int32_t w, h;
+      if (!supported(s) || !orc_varblock_size(s, &w, &h)) { free(covered); return ORC_E_STRATEGY; }
+      int32_t cx = w / 8, cy = h / 8;
+      if (bx % cx || by % cy || bx + cx > Wb || by + cy > Hb) { free(covered); return ORC_E_ALIGN; }
+      for (int32_t j = 0; j < cy; ++j)
+        for (int32_t i = 0; i < cx; ++i) {
+          if (covered[(by + j) * Wb + bx + i]) { free(covered); return ORC_E_ALIGN; }
+          covered[(by + j) * Wb + bx + i] = 1;
+          if (owner) owner[(by + j) * Wb + bx + i] = n;
+        }
+      list[n].bx0 = bx;
+      list[n].by0 = by;
+      list[n].s = s;
+      ++n;
+    }
+  free(covered);
+  *count = n;
+  return ORC_OK;
+}
+
+/* F.3 bias adjustment of a quantized AC value. */
+static const double kOneBias[3] = {0.05465007330715401, 0.07005449891748593,
+                                   0.049935103337343655};
+static double ac_bias(int32_t q, int c) {
+  if (abs(q) <= 1) return q * (1.0 - kOneBias[c]);
+  return q - 0.145 / q;
+}
+
+static int check_params(const orc_params* p) {
+  if (p->xsize <= 0 || p->ysize <= 0) return ORC_E_SIZE;
+  if (p->global_scale < 1 || p->global_scale > (1 << 16)) return ORC_E_PARAM;
+  if (p->epf_sigma_max < 0 || p->epf_sigma_max > 672) return ORC_E_PARAM;
+  if (p->epf_sigma_shift < 0 || p->epf_sigma_shift > 8) return ORC_E_PARAM;
+  if (p->epf_iters < 0 || p->target_nits_div50 < 1) return ORC_E_PARAM;
+  /* J.2.5 divides by the sum of weights; the centre weight is exactly 1, so a
+   * threshold above 1 would leave nothing to divide by. */
+  if (!(p->epf_weight_min <= 1.0)) return ORC_E_PARAM;
+  for (int c = 0; c < 3; ++c)
+    if (p->extra_levels[c] < 0 || p->extra_levels[c] > 3) return ORC_E_PARAM;
+  return ORC_OK;
+}
+
+int orc_reconstruct(const orc_params* p, const int32_t* const ac[3], const int32_t* const dc[3],
+                    const uint8_t* strategy, const uint8_t* qf_minus_1, const float* cfl_kx,
+                    const float* cfl_kb, double* xyb) {
+  int st = check_params(p);
+  if (st) return st;
+  const int32_t W = p->xsize, H = p->ysize;
+  const int32_t Wb = (W + 7) / 8, Hb = (H + 7) / 8;
+  const int32_t PW = 8 * Wb;          /* padded plane width */
+  const int32_t Wt = (W + 63) / 64;   /* CfL tiles per row */
+
+  /* Dequantization matrices per transform type and channel. */
+  double (*dq)[3][1024] = (double (*)[3][1024])malloc(sizeof(double) * 12 * 3 * 1024);
+  if (!dq) return ORC_E_SIZE;
+  for (int s = 0; s < 12; ++s)
+    for (int c = 0; c < 3; ++c) {
+      st = orc_dequant_matrix(s, c, dq[s][c]);
+      if (st) { free(dq); return st; }
+    }
+
+  /* F.2: dequantized DC, then Annex G on the DC with the DC factors. */
+  double* dcq = (double*)malloc(sizeof(double) * 3 * Wb * Hb);
+  varblock* list = (varblock*)malloc(sizeof(varblock) * Wb * Hb);
+  double* pad = (double*)malloc(sizeof(double) * 3 * PW * 8 * Hb);
+  if (!dcq || !list || !pad) { free(dq); free(dcq); free(list); free(pad); return ORC_E_SIZE; }
+  for (int c = 0; c < 3; ++c)
+    for (int32_t i = 0; i < Wb * Hb; ++i)
+      dcq[c * Wb * Hb + i] = p->dc_mul[c] * dc[c][i] / (double)(1 << p->extra_levels[c]);
+  for (int32_t i = 0; i < Wb * Hb; ++i) {
+    double Y = dcq[1 * Wb * Hb + i];
+    dcq[0 * Wb * Hb + i] += p->kx_dc * Y;
+    dcq[2 * Wb * Hb + i] += p->kb_dc * Y;
+  }
+
+  int32_t nvb = 0;
+  /* The quant field values are bytes, inside the [0, 256) range of C.5.5. */
+  st = scan_varblocks(Wb, Hb, strategy, list, &nvb, NULL);
+  if (st) { free(dq); free(dcq); free(list); free(pad); return st; }
+
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int32_t v = 0; v < nvb; ++v) {
+    const varblock vb = list[v];
+    int32_t bx, by;
+    orc_varblock_size(vb.s, &bx, &by);
+    const int32_t cx = bx / 8, cy = by / 8;
+    /* C.5.5: AcMul of the varblock, from its top-left quant field value. */
+    const double acmul =
+        65536.0 / ((double)p->global_scale * (1.0 + qf_minus_1[vb.by0 * Wb + vb.bx0]));
+    /* Annex G: the 64 x 64 region containing the varblock. */
+    const int32_t tile = (vb.by0 * 8 / 64) * Wt + vb.bx0 * 8 / 64;
+    const double kx = cfl_kx[tile], kb = cfl_kb[tile];
+    double K[3][1024];
+    for (int c = 0; c < 3; ++c) {
+      /* F.3: bias, AcMul, dequantization matrix for every HF coefficient. */
+      for (int32_t y = 0; y < by; ++y)
+        for (int32_t x = 0; x < bx; ++x) {
+          int32_t q = ac[c][(size_t)(8 * vb.by0 + y) * PW + 8 * vb.bx0 + x];
+          K[c][y * bx + x] = ac_bias(q, c) * acmul * dq[vb.s][c][y * bx + x];
+        }
+      /* F.2 last paragraph + I.2.7: the LLF corner from the DC samples. */
+      double D[16], L[16];
+      for (int32_t j = 0; j < cy; ++j)
+        for (int32_t i = 0; i < cx; ++i)
+          D[j * cx + i] = dcq[c * Wb * Hb + (vb.by0 + j) * Wb + vb.bx0 + i];
+      orc_llf_from_dc(vb.s, D, L);
+      for (int32_t y = 0; y < cy; ++y)
+        for (int32_t x = 0; x < cx; ++x) K[c][y * bx + x] = L[y * cx + x];
+    }
+    /* Annex G on the AC coefficients, with the tile's factors. */
+    for (int32_t y = 0; y < by; ++y)
+      for (int32_t x = 0; x < bx; ++x) {
+        if (x < cx && y < cy) continue;
+        double Y = K[1][y * bx + x];
+        K[0][y * bx + x] += kx * Y;
+        K[2][y * bx + x] += kb * Y;
+      }
+    /* Annex I: inverse transform, written at the varblock's pixels. */
+    for (int c = 0; c < 3; ++c) {
+      double S[1024];
+      orc_inverse_transform(vb.s, K[c], S);
+      for (int32_t y = 0; y < by; ++y)
+        for (int32_t x = 0; x < bx; ++x)
+          pad[(size_t)c * PW * 8 * Hb + (size_t)(8 * vb.by0 + y) * PW + 8 * vb.bx0 + x] =
+              S[y * bx + x];
+    }
+  }
+  /* 6.2: crop to xsize x ysize. */
+  for (int c = 0; c < 3; ++c)
+    for (int32_t y = 0; y < H; ++y)
+      for (int32_t x = 0; x < W; ++x)
+        xyb[(size_t)c * W * H + (size_t)y * W + x] =
+            pad[(size_t)c * PW * 8 * Hb + (size_t)y * PW + x];
+  free(dq);
+  free(dcq);
+  free(list);
+  free(pad);
+  return ORC_OK;
+}
+
+/* ======================================================================= */
+/* Mirroring (6.5)                                                         */
+/* ======================================================================= */
+
+static int32_t mirror(int32_t coord, int32_t size) {
+  while (coord < 0 || coord >= size) {
+    if (coord < 0) coord = -coord - 1;
+    else coord = 2 * size - 1 - coord;
+  }
+  return coord;
+}
+
+/* ======================================================================= */
+/* Edge-preserving filter (J.2)                                            */
+/* ======================================================================= */
+
+/* x >> s of 5.3.1: floor(x / 2^s). */
+static int64_t shr_floor(int64_t x, int s) {
+  int64_t d = (int64_t)1 << s;
+  int64_t q = x / d;
+  if ((x % d) != 0 && x < 0) --q;
+  return q;
+}
+
+/* Weight(sad, mul) of J.2.4; MakeBinary32 of 5.2. */
+float orc_epf_weight(int32_t sad, int32_t mul) {
+  int64_t prescaled = (int64_t)(sad < 507 ? sad : 507) * 64;
+  int64_t high16 = shr_floor(prescaled * mul, 16) + (127 << (23 - 16));
+  uint32_t bits = (uint32_t)(high16 * 65536);
+  float w;
+  memcpy(&w, &bits, sizeof(w));
+  return w;
+}
+
+/* mul_table of J.2.4.  kSigmaShift is not defined by the draft; it is a
+ * parameter here (default 0).  Reading of the interpolation step: the printed
+ * division is truncated toward zero (Idiv), so every entry is an integer. */
+int orc_epf_mul_table(int32_t shift, int32_t* table) {
+  const int gap = 4;
+  int32_t mul = -32768;
+  for (int i = 0; i <= 672; ++i) table[i] = 0;
+  for (int32_t sigma = 16; sigma <= 672; sigma += gap) {
+    for (; mul < 0; ++mul) {
+      float w = orc_epf_weight(sigma >> shift, mul);
+      if (w > 0.5f) break;
+    }
+    table[sigma] = mul;
+  }
+  for (int32_t sigma = 16; sigma < 672; sigma += gap) {
+    int32_t diff = table[sigma + gap] - table[sigma];
+    int32_t step = diff / gap; /* C division truncates toward zero: Idiv */
+    for (int i = 1; i < gap; ++i) table[sigma + i] = table[sigma] + i * step;
+  }
+  return ORC_OK;
+}
+
+int orc_epf_pass(const orc_params* p, const uint8_t* strategy, const uint8_t* qf_minus_1,
+                 const uint8_t* sharpness, const double* in, double* out,
+                 uint8_t* guide_out, int32_t* sigma_out) {
+  int st = check_params(p);
+  if (st) return st;
+  const int32_t W = p->xsize, H = p->ysize;
+  const int32_t Wb = (W + 7) / 8, Hb = (H + 7) / 8;
+  const size_t plane = (size_t)W * H;
+
+  varblock* list = (varblock*)malloc(sizeof(varblock) * Wb * Hb);
+  int32_t* owner = (int32_t*)malloc(sizeof(int32_t) * Wb * Hb);
+  uint8_t* guide = (uint8_t*)malloc(3 * plane);
+  double* brange = (double*)malloc(sizeof(double) * Wb * Hb);
+  double* vrange = (double*)malloc(sizeof(double) * Wb * Hb);
+  int32_t* sigma = (int32_t*)malloc(sizeof(int32_t) * Wb * Hb);
+  int32_t mul_table[673];
+  int32_t nvb = 0;
+  if (!list || !owner || !guide || !brange || !vrange || !sigma) st = ORC_E_SIZE;
+  if (!st) st = scan_varblocks(Wb, Hb, strategy, list, &nvb, owner);
+  /* C.5.6: sharpness indexes the 8-entry epf_sharp_lut. */
+  for (int32_t b = 0; !st && b < Wb * Hb; ++b)
+    if (sharpness[b] > 7) st = ORC_E_PARAM;
+  if (st) {
+    free(list); free(owner); free(guide); free(brange); free(vrange); free(sigma);
+    return st;
+  }
+  orc_epf_mul_table(p->epf_sigma_shift, mul_table);
+
+  /* J.2.1: intensity_multiplier3 = cbrt(target_nits_div50 * 50 / 250). */
+  const double im3 = cbrt(p->target_nits_div50 * 50.0 / 250.0);
+  double minv[3];
+  for (int c = 0; c < 3; ++c) minv[c] = (c != 0 ? 0.0 : -0.03) * im3;
+
+  /* J.2.2: guide samples.  The draft stores them as unsigned 8-bit values and
+   * does not say how the real value is rounded; reading: the clamped value is
+   * floored, and this one expression is evaluated in binary32, the precision
+   * of the GPU path, so that both take the integer decision alike. */
+#pragma omp parallel for
+  for (int32_t y = 0; y < H; ++y)
+    for (int32_t x = 0; x < W; ++x)
+      for (int c = 0; c < 3; ++c) {
+        float sc = ((float)in[c * plane + (size_t)y * W + x] - (float)minv[c]) *
+                   (float)p->epf_scale[c];
+        float g = sc < 0.0f ? 0.0f : (sc > 255.0f ? 255.0f : sc);
+        guide[c * plane + (size_t)y * W + x] = (uint8_t)floorf(g);
+      }
+
+  /* J.2.4: r[c] = max - min of `scaled` over each 8 x 8 block (the pixels of
+   * the block inside the frame), all_r = max over channels. */
+  for (int32_t by = 0; by < Hb; ++by)
+    for (int32_t bx = 0; bx < Wb; ++bx) {
+      double r = 0.0;
+      for (int c = 0; c < 3; ++c) {
+        double lo = INFINITY, hi = -INFINITY;
+        for (int32_t y = 8 * by; y < 8 * by + 8 && y < H; ++y)
+          for (int32_t x = 8 * bx; x < 8 * bx + 8 && x < W; ++x) {
+            double sc = (in[c * plane + (size_t)y * W + x] - minv[c]) * p->epf_scale[c];
+            if (sc < lo) lo = sc;
+            if (sc > hi) hi = sc;
+          }
+        if (hi - lo > r) r = hi - lo;
+      }
+      brange[by * Wb + bx] = r;
+    }
+  /* range = the largest all_r within the varblock. */
+  for (int32_t v = 0; v < nvb; ++v) {
+    int32_t bx, by;
+    orc_varblock_size(list[v].s, &bx, &by);
+    double r = 0.0;
+    for (int32_t j = 0; j < by / 8; ++j)
+      for (int32_t i = 0; i < bx / 8; ++i) {
+        double b = brange[(list[v].by0 + j) * Wb + list[v].bx0 + i];
+        if (b > r) r = b;
+      }
+    for (int32_t j = 0; j < by / 8; ++j)
+      for (int32_t i = 0; i < bx / 8; ++i) vrange[(list[v].by0 + j) * Wb + list[v].bx0 + i] = r;
+  }
+  /* sigma per block.  quant = 1 / AcMul is written as
+   * global_scale * (1 + dv) / 65536, its exact value. */
+  for (int32_t b = 0; b < Wb * Hb; ++b) {
+    double range = vrange[b];
+    if (range > p->epf_range_max) range = p->epf_range_max;
+    double s = range * p->epf_range_mul * p->epf_sharp_lut[sharpness[b]];
+    double quant = (double)p->global_scale * (1.0 + qf_minus_1[b]) / 65536.0;
+    if (quant * p->epf_quant_mul < s) s = quant * p->epf_quant_mul;
+    if ((double)p->epf_sigma_max < s) s = p->epf_sigma_max;
+    sigma[b] = (int32_t)(s < 0 ? -floor(-s) : floor(s)); /* truncate */
+  }
+
+  /* J.2.3 + J.2.5.  Reading: mul_table is defined for sigma >= 16 only; a
+   * pixel whose sigma is below 16 is passed through unfiltered. */
+#pragma omp parallel for schedule(dynamic, 4)
+  for (int32_t y = 0; y < H; ++y)
+    for (int32_t x = 0; x < W; ++x) {
+      const int32_t b = (y / 8) * Wb + x / 8;
+      if (sigma[b] < 16) {
+        for (int c = 0; c < 3; ++c)
+          out[c * plane + (size_t)y * W + x] = in[c * plane + (size_t)y * W + x];
+        continue;
+      }
+      const int32_t mul = mul_table[sigma[b]];
+      int32_t sad[56];
+      for (int i = 0; i < 56; ++i) sad[i] = 0;
+      for (int c = 0; c < 3; ++c)
+        for (int32_t cy = -3; cy <= 3; ++cy)
+          for (int32_t cx = -3; cx <= 4; ++cx) {
+            int32_t i = (cy + 3) * 8 + cx + 3;
+            int32_t d = 0;
+            for (int32_t iy = -1; iy <= 1; ++iy)
+              for (int32_t ix = -1; ix <= 2; ++ix) {
+                int32_t g0 = guide[c * plane + (size_t)mirror(y + iy, H) * W + mirror(x + ix, W)];
+                int32_t g1 = guide[c * plane + (size_t)mirror(y + cy + iy, H) * W +
+                                   mirror(x + cx + ix, W)];
+                d += abs(g0 - g1);
+              }
+            sad[i] += d;
+          }
+      double weights[56];
+      for (int i = 0; i < 56; ++i) {
+        weights[i] = orc_epf_weight(sad[i], mul);
+        if (weights[i] < p->epf_weight_min) weights[i] = 0.0;
+      }
+      double wsum[3] = {0, 0, 0}, sw[3] = {0, 0, 0};
+      int i = 0;
+      for (int32_t cy = -3; cy <= 3; ++cy)
+        for (int32_t cx = -3; cx <= 4; ++cx) {
+          double w = weights[i++];
+          for (int c = 0; c < 3; ++c) {
+            wsum[c] += in[c * plane + (size_t)mirror(y + cy, H) * W + mirror(x + cx, W)] * w;
+            sw[c] += w;
+          }
+        }
+      for (int c = 0; c < 3; ++c) out[c * plane + (size_t)y * W + x] = wsum[c] / sw[c];
+    }
+
+  if (guide_out) memcpy(guide_out, guide, 3 * plane);
+  if (sigma_out) memcpy(sigma_out, sigma, sizeof(int32_t) * Wb * Hb);
+  free(list); free(owner); free(guide); free(brange); free(vrange); free(sigma);
+  return ORC_OK;
+}
+
+/* ======================================================================= */
+/* Gaborish (J.4)                                                          */
+/* ======================================================================= */
+
+/* Reading: the weights are the loop-filter fields themselves; the printed
+ * factor 10^-6 contradicts the field defaults (0.115..., 0.061...), which are
+ * already fractions of the centre weight. */
+int orc_gaborish(const orc_params* p, const double* in, double* out) {
+  int st = check_params(p);
+  if (st) return st;
+  const int32_t W = p->xsize, H = p->ysize;
+  const size_t plane = (size_t)W * H;
+  for (int c = 0; c < 3; ++c) {
+    const double norm = 1.0 + 4.0 * p->gab_w1[c] + 4.0 * p->gab_w2[c];
+    double k[3][3];
+    for (int dy = -1; dy <= 1; ++dy)
+      for (int dx = -1; dx <= 1; ++dx) {
+        int taxi = abs(dx) + abs(dy);
+        double w = taxi == 0 ? 1.0 : (taxi == 1 ? p->gab_w1[c] : p->gab_w2[c]);
+        k[dy + 1][dx + 1] = w / norm;
+      }
+#pragma omp parallel for
+    for (int32_t y = 0; y < H; ++y)
+      for (int32_t x = 0; x < W; ++x) {
+        double acc = 0.0;
+        for (int dy = -1; dy <= 1; ++dy)
+          for (int dx = -1; dx <= 1; ++dx)
+            acc += k[dy + 1][dx + 1] *
+                   in[c * plane + (size_t)mirror(y + dy, H) * W + mirror(x + dx, W)];
+        out[c * plane + (size_t)y * W + x] = acc;
+      }
+  }
+  return ORC_OK;
+}
+
+/* ======================================================================= */
+/* XYB -> RGB (L.2)                                                        */
+/* ======================================================================= */
+
+int orc_xyb_to_rgb(const orc_params* p, const double* xyb, double* rgb) {
+  int st = check_params(p);
+  if (st) return st;
+  const size_t plane = (size_t)p->xsize * p->ysize;
+  const double scale = p->target_nits_div50 * 50.0 / 250.0;
+#pragma omp parallel for
+  for (int64_t i = 0; i < (int64_t)plane; ++i) {
+    double X = xyb[i], Y = xyb[plane + i], B = xyb[2 * plane + i];
+    double g[3] = {Y + X, Y - X, B};
+    double mix[3];
+    for (int c = 0; c < 3; ++c) mix[c] = g[c] * g[c] * g[c] + p->opsin_bias[c];
+    for (int r = 0; r < 3; ++r) {
+      double v = 0.0;
+      for (int c = 0; c < 3; ++c) v += p->opsin_inv[r * 3 + c] * mix[c];
+      /* Divided by target_nits_div50 * 50 / 250, then by 255 for [0, 1]. */
+      rgb[r * plane + i] = v / scale / 255.0;
+    }
+  }
+  return ORC_OK;
+}
+
+/* Reading for 8- and 16-bit output: the sRGB transfer function
+ * (IEC 61966-2-1) applied to the linear value clamped to [0, 1], then
+ * Q_b(v) = floor(v * (2^b - 1) + 0.5). */
+int orc_quantize_srgb(int32_t bits, int64_t n, const double* lin, uint16_t* out) {
+  if (bits != 8 && bits != 16) return ORC_E_PARAM;
+  const double maxv = (double)((1 << bits) - 1);
+  for (int64_t i = 0; i < n; ++i) {
+    double v = lin[i];
+    v = v < 0.0 ? 0.0 : (v > 1.0 ? 1.0 : v);
+    double e = v <= 0.0031308 ? 12.92 * v : 1.055 * pow(v, 1.0 / 2.4) - 0.055;
+    out[i] = (uint16_t)floor(e * maxv + 0.5);
+  }
+  return ORC_OK;
+}
+
+/* ======================================================================= */
+/* Whole path (9.7-9.13)                                                   */
+/* ======================================================================= */
+
+int orc_decode(const orc_params* p, const int32_t* const ac[3], const int32_t* const dc[3],
+               const uint8_t* strategy, const uint8_t* qf_minus_1, const uint8_t* sharpness,
+               const float* cfl_kx, const float* cfl_kb, double* rgb) {
+  int st = check_params(p);
+  if (st) return st;
+  const size_t n = 3 * (size_t)p->xsize * p->ysize;
+  double* a = (double*)malloc(sizeof(double) * n);
+  double* b = (double*)malloc(sizeof(double) * n);
+  if (!a || !b) { free(a); free(b); return ORC_E_SIZE; }
+  st = orc_reconstruct(p, ac, dc, strategy, qf_minus_1, cfl_kx, cfl_kb, a);
+  for (int it = 0; !st && it < p->epf_iters; ++it) {
+    st = orc_epf_pass(p, strategy, qf_minus_1, sharpness, a, b, NULL, NULL);
+    double* t = a; a = b; b = t;
+  }
+  if (!st && p->gab) {
+    st = orc_gaborish(p, a, b);
+    double* t = a; a = b; b = t;
+  }
+  if (!st) st = orc_xyb_to_rgb(p, a, rgb);
+  free(a);
+  free(b);
+  return st;
+}

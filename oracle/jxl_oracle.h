@@ -1,0 +1,151 @@
+/*
+ * jxl_oracle.h -- plain FP64 CPU oracle for JPEG XL VarDCT pixel reconstruction.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check and the CPU
+ * baseline leg of the benchmark may load this library.  The product path
+ * (the HIP library and its binding) never links, imports or calls it, and the
+ * two share no code, headers or tables.
+ *
+ * Every function follows the JPEG XL Committee Draft (ISO/IEC 18181 CD,
+ * 2019-08-05) and cites the clause it implements.  Arithmetic is double
+ * precision throughout ("real numbers", clause 5.4), except the one
+ * expression the edge-preserving filter turns into an unsigned 8-bit guide
+ * sample (J.2.2), which is evaluated in binary32 on purpose (see
+ * orc_epf_pass).
+ *
+ * Conventions shared by all entry points:
+ *   - images are planar, row-major, channel c in {0: X, 1: Y, 2: B};
+ *   - a frame of xsize x ysize pixels has Wb = ceil(xsize/8) by Hb = ceil(ysize/8)
+ *     blocks; coefficient planes are [8*Hb][8*Wb], per-block maps [Hb][Wb];
+ *   - coefficient (x, y) of the varblock whose top-left block is (bx0, by0)
+ *     is stored at plane position (8*bx0 + x, 8*by0 + y); x is the horizontal
+ *     frequency index;
+ *   - the DctSelect map follows C.5.4: only the entry at a varblock's
+ *     top-left block is read; entries of other covered blocks are ignored.
+ * Return values: 0 on success, a negative ORC_E_* code when the input is
+ * ill-formed in the sense of the draft (C.5.4, C.6.1) or out of range.
+ */
+#ifndef JXL_ORACLE_H
+#define JXL_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  ORC_OK = 0,
+  ORC_E_SIZE = -1,      /* xsize or ysize not positive */
+  ORC_E_STRATEGY = -2,  /* DctSelect value outside the C.5.4 table or not supported */
+  ORC_E_ALIGN = -3,     /* varblock not naturally aligned, out of bounds, or overlapping (C.5.4) */
+  ORC_E_QUANT = -4,     /* quant field value outside [0, 256) (C.5.5) */
+  ORC_E_DEQUANT = -5,   /* dequantization matrix entry not positive and finite (C.6.1) */
+  ORC_E_PARAM = -6      /* frame parameter outside its range */
+};
+
+/* Transform types, numbered as in the C.5.4 table. */
+enum {
+  ORC_DCT8 = 0, ORC_IDENTITY = 1, ORC_DCT2 = 2, ORC_DCT4 = 3, ORC_DCT16 = 4,
+  ORC_DCT32 = 5, ORC_DCT16X8 = 6, ORC_DCT8X16 = 7, ORC_DCT32X8 = 8,
+  ORC_DCT8X32 = 9, ORC_DCT32X16 = 10, ORC_DCT16X32 = 11, ORC_DCT4X8 = 12,
+  ORC_DCT8X4 = 13, ORC_AFV = 14
+};
+
+/* Frame parameters decoded from the headers (C.2, C.4, C.10, A.4.5, L.2). */
+typedef struct {
+  int32_t xsize, ysize;
+  int32_t global_scale;        /* global_scale_minus_1 + 1 (C.4.2) */
+  double  dc_mul[3];           /* mX_DC, mY_DC, mB_DC (C.4.1) */
+  int32_t extra_levels[3];     /* extra_levels_xyb (C.5.2) */
+  double  kx_dc, kb_dc;        /* DC chroma-from-luma factors, already as kX, kB (Annex G) */
+  int32_t gab;                 /* loop_filter.gab (C.10) */
+  double  gab_w1[3], gab_w2[3];/* Gaborish weights per channel (C.10) */
+  int32_t epf_iters;           /* number of edge-preserving filter passes; 0 = off */
+  double  epf_weight_min;
+  double  epf_scale[3];
+  double  epf_sharp_lut[8];
+  double  epf_range_max, epf_range_mul, epf_quant_mul;
+  int32_t epf_sigma_max;
+  int32_t epf_sigma_shift;     /* kSigmaShift of J.2.4 */
+  double  opsin_inv[9];        /* inverse opsin absorbance matrix, row-major (L.2) */
+  double  opsin_bias[3];
+  int32_t target_nits_div50;   /* ImageMetadata (A.4.5) */
+} orc_params;
+
+/* Fills the defaults the draft gives for every field (C.4, C.10, L.2, A.4.5). */
+void orc_params_default(orc_params* p, int32_t xsize, int32_t ysize);
+
+/* Varblock size in pixels of a transform type (I.2.5); returns 0 if unknown. */
+int orc_varblock_size(int strategy, int32_t* bx, int32_t* by);
+
+/* ---- transforms (Annex I) ---------------------------------------------- */
+/* T_N (N in {1,2,4,8,16,32}): inverse 1-D transform of I.2.1 as a matrix,
+ * out[n*N + k] = weight of input coefficient k in output sample n. */
+int orc_idct_matrix(int32_t N, double* out);
+/* F_N: forward 1-D transform of I.2.1 as a matrix, out[k*N + n]. */
+int orc_fdct_matrix(int32_t N, double* out);
+/* I(N, u), D(N, u), ScaleF(N, n, x) of I.2.6.1. */
+double orc_scale_I(int32_t N, int32_t u);
+double orc_scale_D(int32_t N, int32_t u);
+double orc_scalef(int32_t N, int32_t n, int32_t x);
+/* Inverse transform of one varblock (I.2.4): coefficients [by][bx] -> samples [by][bx]. */
+int orc_inverse_transform(int strategy, const double* coeffs, double* samples);
+/* Forward transform of one varblock (I.2.3); used by round-trip pins only. */
+int orc_forward_transform(int strategy, const double* samples, double* coeffs);
+/* LLF coefficients from the downsampled (DC) image (I.2.7, N = 8):
+ * dc [cy][cx] -> llf [cy][cx]. */
+int orc_llf_from_dc(int strategy, const double* dc, double* llf);
+/* Downsampled image from LF coefficients (I.2.6, N = 8): llf [cy][cx] -> dc [cy][cx]. */
+int orc_dc_from_llf(int strategy, const double* llf, double* dc);
+
+/* ---- dequantization (C.6.1, F.3) --------------------------------------- */
+/* Default dequantization matrix of a transform type and channel, [by][bx]. */
+int orc_dequant_matrix(int strategy, int c, double* out);
+
+/* ---- reconstruction (F, G, I) ------------------------------------------ */
+/* Quantized DC/AC planes and side maps -> XYB samples, cropped to xsize x ysize.
+ * cfl_kx/cfl_kb: per 64x64 tile kX and kB of Annex G, [ceil(ysize/64)][ceil(xsize/64)]. */
+int orc_reconstruct(const orc_params* p,
+                    const int32_t* const ac[3], const int32_t* const dc[3],
+                    const uint8_t* strategy, const uint8_t* qf_minus_1,
+                    const float* cfl_kx, const float* cfl_kb,
+                    double* xyb /* [3][ysize][xsize] */);
+
+/* ---- loop filters (Annex J) -------------------------------------------- */
+/* mul_table of J.2.4 for sigma in [0, 672]; entries below 16 are 0. */
+int orc_epf_mul_table(int32_t sigma_shift, int32_t* table /* [673] */);
+/* Weight(sad, mul) of J.2.4 as its binary32 value. */
+float orc_epf_weight(int32_t sad, int32_t mul);
+/* One edge-preserving filter pass (J.2) over a cropped XYB frame.
+ * guide_out [3][ysize][xsize] and sigma_out [Hb][Wb] may be NULL. */
+int orc_epf_pass(const orc_params* p, const uint8_t* strategy,
+                 const uint8_t* qf_minus_1, const uint8_t* sharpness,
+                 const double* in, double* out,
+                 uint8_t* guide_out, int32_t* sigma_out);
+/* Gaborish (J.4). */
+int orc_gaborish(const orc_params* p, const double* in, double* out);
+
+/* ---- colour (Annex L) -------------------------------------------------- */
+/* XYB -> linear RGB of L.2, divided by 255 ("[0,1]-scaled"). */
+int orc_xyb_to_rgb(const orc_params* p, const double* xyb, double* rgb);
+/* sRGB transfer function and rounding to 'bits' (8 or 16) per sample. */
+int orc_quantize_srgb(int32_t bits, int64_t n, const double* lin, uint16_t* out);
+
+/* ---- whole path -------------------------------------------------------- */
+/* Reconstruct, epf_iters EPF passes, Gaborish (if p->gab), XYB -> RGB.
+ * rgb: [3][ysize][xsize] of [0,1]-scaled linear RGB. */
+int orc_decode(const orc_params* p,
+               const int32_t* const ac[3], const int32_t* const dc[3],
+               const uint8_t* strategy, const uint8_t* qf_minus_1,
+               const uint8_t* sharpness,
+               const float* cfl_kx, const float* cfl_kb,
+               double* rgb);
+
+/* Number of OpenMP threads the oracle runs with (1 when built without OpenMP). */
+int orc_num_threads(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

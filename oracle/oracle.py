@@ -1,0 +1,293 @@
+"""ctypes front end of the FP64 oracle (test infrastructure only).
+
+Only tests/, the smoke check and the CPU-baseline leg of bench.py may import
+this module.  It loads oracle/liboracle.so (building it with gcc when it is
+missing) and marshals numpy arrays; all arithmetic is in jxl_oracle.c.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+from . import build as _build
+
+_LIB = None
+
+
+class OrcParams(C.Structure):
+    _fields_ = [
+        ("xsize", C.c_int32), ("ysize", C.c_int32),
+        ("global_scale", C.c_int32),
+        ("dc_mul", C.c_double * 3),
+        ("extra_levels", C.c_int32 * 3),
+        ("kx_dc", C.c_double), ("kb_dc", C.c_double),
+        ("gab", C.c_int32),
+        ("gab_w1", C.c_double * 3), ("gab_w2", C.c_double * 3),
+        ("epf_iters", C.c_int32),
+        ("epf_weight_min", C.c_double),
+        ("epf_scale", C.c_double * 3),
+        ("epf_sharp_lut", C.c_double * 8),
+        ("epf_range_max", C.c_double), ("epf_range_mul", C.c_double),
+        ("epf_quant_mul", C.c_double),
+        ("epf_sigma_max", C.c_int32),
+        ("epf_sigma_shift", C.c_int32),
+        ("opsin_inv", C.c_double * 9),
+        ("opsin_bias", C.c_double * 3),
+        ("target_nits_div50", C.c_int32),
+    ]
+
+
+_i32p = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
+_u8p = np.ctypeslib.ndpointer(dtype=np.uint8, flags="C_CONTIGUOUS")
+_f32p = np.ctypeslib.ndpointer(dtype=np.float32, flags="C_CONTIGUOUS")
+_f64p = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
+_u16p = np.ctypeslib.ndpointer(dtype=np.uint16, flags="C_CONTIGUOUS")
+
+
+def lib():
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(_build.LIB):
+            _build.build()
+        L = C.CDLL(_build.LIB)
+        P = C.POINTER(OrcParams)
+        L.orc_params_default.argtypes = [P, C.c_int32, C.c_int32]
+        L.orc_varblock_size.argtypes = [C.c_int, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
+        L.orc_idct_matrix.argtypes = [C.c_int32, _f64p]
+        L.orc_fdct_matrix.argtypes = [C.c_int32, _f64p]
+        for f in ("orc_scale_I", "orc_scale_D"):
+            getattr(L, f).argtypes = [C.c_int32, C.c_int32]
+            getattr(L, f).restype = C.c_double
+        L.orc_scalef.argtypes = [C.c_int32, C.c_int32, C.c_int32]
+        L.orc_scalef.restype = C.c_double
+        L.orc_inverse_transform.argtypes = [C.c_int, _f64p, _f64p]
+        L.orc_forward_transform.argtypes = [C.c_int, _f64p, _f64p]
+        L.orc_llf_from_dc.argtypes = [C.c_int, _f64p, _f64p]
+        L.orc_dc_from_llf.argtypes = [C.c_int, _f64p, _f64p]
+        L.orc_dequant_matrix.argtypes = [C.c_int, C.c_int, _f64p]
+        ptr3 = C.c_void_p * 3
+        L.orc_reconstruct.argtypes = [P, ptr3, ptr3, _u8p, _u8p, _f32p, _f32p, _f64p]
+        L.orc_epf_mul_table.argtypes = [C.c_int32, _i32p]
+        L.orc_epf_weight.argtypes = [C.c_int32, C.c_int32]
+        L.orc_epf_weight.restype = C.c_float
+        L.orc_epf_pass.argtypes = [P, _u8p, _u8p, _u8p, _f64p, _f64p, C.c_void_p, C.c_void_p]
+        L.orc_gaborish.argtypes = [P, _f64p, _f64p]
+        L.orc_xyb_to_rgb.argtypes = [P, _f64p, _f64p]
+        L.orc_quantize_srgb.argtypes = [C.c_int32, C.c_int64, _f64p, _u16p]
+        L.orc_decode.argtypes = [P, ptr3, ptr3, _u8p, _u8p, _u8p, _f32p, _f32p, _f64p]
+        L.orc_num_threads.restype = C.c_int
+        _LIB = L
+    return _LIB
+
+
+class OracleError(RuntimeError):
+    pass
+
+
+def _check(st):
+    if st != 0:
+        raise OracleError(f"oracle returned status {st}")
+
+
+# Transform types in the order of the C.5.4 table.
+STRATEGY_NAMES = ["DCT8", "IDENTITY", "DCT2", "DCT4", "DCT16", "DCT32", "DCT16X8",
+                  "DCT8X16", "DCT32X8", "DCT8X32", "DCT32X16", "DCT16X32",
+                  "DCT4X8", "DCT8X4", "AFV"]
+SUPPORTED = list(range(12))
+
+
+def varblock_size(s):
+    bx, by = C.c_int32(), C.c_int32()
+    if not lib().orc_varblock_size(s, C.byref(bx), C.byref(by)):
+        raise OracleError(f"unknown transform type {s}")
+    return bx.value, by.value
+
+
+def params(xsize, ysize, **overrides):
+    """Oracle parameter struct: the draft's defaults, then `overrides`."""
+    p = OrcParams()
+    lib().orc_params_default(C.byref(p), int(xsize), int(ysize))
+    for k, v in overrides.items():
+        cur = getattr(p, k)
+        if isinstance(cur, C.Array):
+            arr = np.asarray(v, dtype=np.float64).ravel()
+            if len(arr) != len(cur):
+                raise ValueError(k)
+            for i, x in enumerate(arr):
+                cur[i] = type(cur[0])(x) if not isinstance(cur[0], float) else float(x)
+        else:
+            setattr(p, k, v)
+    return p
+
+
+def idct_matrix(N):
+    out = np.zeros(N * N)
+    _check(lib().orc_idct_matrix(N, out))
+    return out.reshape(N, N)
+
+
+def fdct_matrix(N):
+    out = np.zeros(N * N)
+    _check(lib().orc_fdct_matrix(N, out))
+    return out.reshape(N, N)
+
+
+def scale_I(N, u):
+    return lib().orc_scale_I(N, u)
+
+
+def scale_D(N, u):
+    return lib().orc_scale_D(N, u)
+
+
+def scalef(N, n, x):
+    return lib().orc_scalef(N, n, x)
+
+
+def inverse_transform(s, coeffs):
+    bx, by = varblock_size(s)
+    K = np.ascontiguousarray(coeffs, dtype=np.float64).reshape(by, bx)
+    out = np.zeros((by, bx))
+    _check(lib().orc_inverse_transform(s, K, out))
+    return out
+
+
+def forward_transform(s, samples):
+    bx, by = varblock_size(s)
+    S = np.ascontiguousarray(samples, dtype=np.float64).reshape(by, bx)
+    out = np.zeros((by, bx))
+    _check(lib().orc_forward_transform(s, S, out))
+    return out
+
+
+def llf_from_dc(s, dc):
+    bx, by = varblock_size(s)
+    cx, cy = bx // 8, by // 8
+    if s not in (0, 4, 5, 6, 7, 8, 9, 10, 11):
+        cx = cy = 1
+    D = np.ascontiguousarray(dc, dtype=np.float64).reshape(cy, cx)
+    out = np.zeros((cy, cx))
+    _check(lib().orc_llf_from_dc(s, D, out))
+    return out
+
+
+def dc_from_llf(s, llf):
+    bx, by = varblock_size(s)
+    cx, cy = bx // 8, by // 8
+    if s not in (0, 4, 5, 6, 7, 8, 9, 10, 11):
+        cx = cy = 1
+    L = np.ascontiguousarray(llf, dtype=np.float64).reshape(cy, cx)
+    out = np.zeros((cy, cx))
+    _check(lib().orc_dc_from_llf(s, L, out))
+    return out
+
+
+def dequant_matrix(s, c):
+    bx, by = varblock_size(s)
+    out = np.zeros(bx * by)
+    _check(lib().orc_dequant_matrix(s, c, out))
+    return out.reshape(by, bx)
+
+
+def _planes(arrs, dtype):
+    keep = [np.ascontiguousarray(a, dtype=dtype) for a in arrs]
+    ptrs = (C.c_void_p * 3)(*[a.ctypes.data for a in keep])
+    return keep, ptrs
+
+
+def reconstruct(p, frame):
+    """frame: dict with ac (3, 8Hb, 8Wb) int32, dc (3, Hb, Wb) int32,
+    strategy, qf (Hb, Wb) uint8, cfl_kx, cfl_kb float32 tiles.
+    Returns XYB (3, ysize, xsize) float64."""
+    ka, pa = _planes(frame["ac"], np.int32)
+    kd, pd = _planes(frame["dc"], np.int32)
+    out = np.zeros((3, p.ysize, p.xsize))
+    _check(lib().orc_reconstruct(
+        C.byref(p), pa, pd, np.ascontiguousarray(frame["strategy"], np.uint8),
+        np.ascontiguousarray(frame["qf"], np.uint8),
+        np.ascontiguousarray(frame["cfl_kx"], np.float32),
+        np.ascontiguousarray(frame["cfl_kb"], np.float32), out))
+    return out
+
+
+def mul_table(shift=0):
+    t = np.zeros(673, dtype=np.int32)
+    _check(lib().orc_epf_mul_table(shift, t))
+    return t
+
+
+def epf_weight(sad, mul):
+    return lib().orc_epf_weight(int(sad), int(mul))
+
+
+def epf_pass(p, frame, xyb, want_debug=False):
+    """One J.2 pass.  Returns out, or (out, guide u8 (3,H,W), sigma int32 (Hb,Wb))."""
+    xyb = np.ascontiguousarray(xyb, dtype=np.float64)
+    out = np.zeros_like(xyb)
+    Hb, Wb = (p.ysize + 7) // 8, (p.xsize + 7) // 8
+    guide = np.zeros((3, p.ysize, p.xsize), np.uint8)
+    sigma = np.zeros((Hb, Wb), np.int32)
+    _check(lib().orc_epf_pass(
+        C.byref(p), np.ascontiguousarray(frame["strategy"], np.uint8),
+        np.ascontiguousarray(frame["qf"], np.uint8),
+        np.ascontiguousarray(frame["sharpness"], np.uint8), xyb, out,
+        guide.ctypes.data if want_debug else None,
+        sigma.ctypes.data if want_debug else None))
+    if want_debug:
+        return out, guide, sigma
+    return out
+
+
+def gaborish(p, xyb):
+    xyb = np.ascontiguousarray(xyb, dtype=np.float64)
+    out = np.zeros_like(xyb)
+    _check(lib().orc_gaborish(C.byref(p), xyb, out))
+    return out
+
+
+def xyb_to_rgb(p, xyb):
+    xyb = np.ascontiguousarray(xyb, dtype=np.float64)
+    out = np.zeros_like(xyb)
+    _check(lib().orc_xyb_to_rgb(C.byref(p), xyb, out))
+    return out
+
+
+def quantize_srgb(bits, lin):
+    lin = np.ascontiguousarray(lin, dtype=np.float64)
+    out = np.zeros(lin.shape, np.uint16)
+    _check(lib().orc_quantize_srgb(bits, lin.size, lin, out))
+    return out
+
+
+def decode(p, frame):
+    """Whole path: returns [0,1]-scaled linear RGB (3, ysize, xsize) float64."""
+    ka, pa = _planes(frame["ac"], np.int32)
+    kd, pd = _planes(frame["dc"], np.int32)
+    out = np.zeros((3, p.ysize, p.xsize))
+    _check(lib().orc_decode(
+        C.byref(p), pa, pd, np.ascontiguousarray(frame["strategy"], np.uint8),
+        np.ascontiguousarray(frame["qf"], np.uint8),
+        np.ascontiguousarray(frame["sharpness"], np.uint8),
+        np.ascontiguousarray(frame["cfl_kx"], np.float32),
+        np.ascontiguousarray(frame["cfl_kb"], np.float32), out))
+    return out
+
+
+def decode_stages(p, frame):
+    """Whole path with every intermediate kept (for stage-by-stage comparison).
+    Returns dict: recon, epf (list of (out, guide, sigma)), gab, rgb."""
+    res = {"recon": reconstruct(p, frame), "epf": []}
+    cur = res["recon"]
+    for _ in range(p.epf_iters):
+        out, g, s = epf_pass(p, frame, cur, want_debug=True)
+        res["epf"].append((out, g, s))
+        cur = out
+    if p.gab:
+        cur = gaborish(p, cur)
+    res["gab"] = cur
+    res["rgb"] = xyb_to_rgb(p, cur)
+    return res
+
+
+def num_threads():
+    return lib().orc_num_threads()

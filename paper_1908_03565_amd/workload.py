@@ -1,0 +1,175 @@
+"""Seeded synthetic inputs for VarDCT reconstruction.
+
+This module draws entropy-decoded inputs (quantized coefficient planes, DC
+planes, DctSelect, quant field, sharpness and chroma-from-luma maps) and the
+frame-parameter overrides of each workload.  It holds none of the method's
+arithmetic: both the GPU path and the FP64 oracle consume its arrays as they
+are.  Only numpy is imported.
+
+Workloads (the frame shapes and value distributions stand in for decoded
+JPEG XL codestreams; no codestream or image data is involved):
+  c1      256x256, every varblock DCT8x8, quant field 8, CfL 0, Gaborish on,
+          EPF off, seed 0
+  c2      2048x2048, DctSelect drawn per 32x32 region from ten transform types,
+          quant field U{1..32} per varblock, CfL U[-1,1] per 64x64 tile,
+          Gaborish on, EPF 2 passes, seed 2
+  c3      4096x4096, half of the 32x32 regions DCT32x32, the rest as c2, seed 3
+  c4      a batch of 64 frames, sides log-uniform in [256, 3072] rounded to 8,
+          EPF 1 pass, 8-bit sRGB output, seed 4
+  small   the c2 recipe at a size the oracle finishes in seconds
+"""
+import math
+
+import numpy as np
+
+# Transform types by their C.5.4 numbers.
+DCT8, IDENTITY, DCT2, DCT4, DCT16, DCT32 = 0, 1, 2, 3, 4, 5
+DCT16X8, DCT8X16, DCT32X8, DCT8X32, DCT32X16, DCT16X32 = 6, 7, 8, 9, 10, 11
+
+# Varblock size in 8x8 blocks, (columns, rows), of each transform type.
+BLOCKS = {0: (1, 1), 1: (1, 1), 2: (1, 1), 3: (1, 1), 4: (2, 2), 5: (4, 4),
+          6: (2, 1), 7: (1, 2), 8: (4, 1), 9: (1, 4), 10: (4, 2), 11: (2, 4)}
+
+# The ten transform types the mixed workloads draw from.
+MIXED = [DCT8, DCT4, DCT2, IDENTITY, DCT16, DCT32, DCT8X16, DCT16X8, DCT16X32, DCT32X16]
+
+# Frame-parameter overrides common to every workload: global_scale = 32768 so
+# that AcMul = 2 / QF, in [1/16, 2] for QF in [1, 32]; DC multipliers that give
+# XYB extents of about +-0.03 (X) and +-1 (Y, B) for DC values in [-512, 512].
+# With these the XYB samples stay within about |Y + X| <= 2.5, so linear RGB
+# stays within a few times the sRGB range.
+BASE_PARAMS = dict(global_scale=32768, dc_mul=(2.0 ** -14, 2.0 ** -9, 2.0 ** -9),
+                   extra_levels=(0, 0, 0))
+
+
+def _fits(s, wb, hb):
+    cx, cy = BLOCKS[s]
+    return wb % cx == 0 and hb % cy == 0
+
+
+def strategy_map(rng, Wb, Hb, choices, p_dct32=None):
+    """DctSelect per 32x32 region (4x4 blocks): one transform type per region,
+    tiled with its varblocks.  Regions clipped by the frame edge draw among the
+    types whose varblocks tile the clipped region.  Every block of a varblock
+    holds the type (only the top-left entry is read)."""
+    smap = np.zeros((Hb, Wb), np.uint8)
+    for ry in range(0, Hb, 4):
+        for rx in range(0, Wb, 4):
+            wb, hb = min(4, Wb - rx), min(4, Hb - ry)
+            ok = [s for s in choices if _fits(s, wb, hb)]
+            if p_dct32 is not None and _fits(DCT32, wb, hb) and rng.random() < p_dct32:
+                s = DCT32
+            else:
+                pool = ok if p_dct32 is None else [s for s in ok if s != DCT32] or ok
+                s = pool[rng.integers(len(pool))] if pool else DCT8
+            smap[ry:ry + hb, rx:rx + wb] = s
+    return smap
+
+
+def _varblock_geometry(smap):
+    """Per coefficient position: (x, y) inside its varblock and the varblock
+    size in pixels, for a map produced by strategy_map."""
+    Hb, Wb = smap.shape
+    cx = np.vectorize(lambda s: BLOCKS[int(s)][0])(smap).astype(np.int32)
+    cy = np.vectorize(lambda s: BLOCKS[int(s)][1])(smap).astype(np.int32)
+    bxs = np.arange(Wb)[None, :]
+    bys = np.arange(Hb)[:, None]
+    # Varblocks are naturally aligned, so a block's offset inside its varblock
+    # is its index modulo the varblock size (in blocks).
+    offx = (bxs % cx)
+    offy = (bys % cy)
+    px = np.arange(8 * Wb)
+    py = np.arange(8 * Hb)
+    B = lambda a: np.repeat(np.repeat(a, 8, axis=0), 8, axis=1)
+    xin = B(offx) * 8 + (px[None, :] % 8)
+    yin = B(offy) * 8 + (py[:, None] % 8)
+    return xin, yin, B(cx) * 8, B(cy) * 8
+
+
+def frame(W, H, seed, choices=None, p_dct32=None, qf_const=None, cfl_zero=False,
+          epf_iters=2, gab=1, out_format=0, name="frame"):
+    """One synthetic frame as a dict of numpy arrays plus parameter overrides."""
+    rng = np.random.default_rng(seed)
+    Wb, Hb = (W + 7) // 8, (H + 7) // 8
+    choices = MIXED if choices is None else choices
+    smap = strategy_map(rng, Wb, Hb, choices, p_dct32)
+
+    # DC: uniform integers in [-512, 512] per block and channel.
+    dc = rng.integers(-512, 513, size=(3, Hb, Wb), dtype=np.int64).astype(np.int32)
+
+    # AC: Laplacian, scale 4 at the lowest AC frequency falling to 0.5 at the
+    # highest of an 8x8 block: b = max(0.5, 4 * 8^(-(r - 1) / 13)) with
+    # r = 8x/bx + 8y/by; rounded half away from zero; the LLF corner is 0.
+    xin, yin, bxp, byp = _varblock_geometry(smap)
+    r = 8.0 * xin / bxp + 8.0 * yin / byp
+    b = np.maximum(0.5, 4.0 * 8.0 ** (-(r - 1.0) / 13.0))
+    llf = (xin < bxp // 8) & (yin < byp // 8)
+    ac = np.empty((3, 8 * Hb, 8 * Wb), np.int32)
+    for c in range(3):
+        v = rng.laplace(0.0, 1.0, size=b.shape) * b
+        q = np.sign(v) * np.floor(np.abs(v) + 0.5)
+        q[llf] = 0
+        ac[c] = q.astype(np.int32)
+
+    # Quant field (dv = QF - 1): per 8x8 block, then every block of a varblock
+    # takes the value of its top-left block.
+    if qf_const is not None:
+        qf = np.full((Hb, Wb), qf_const - 1, np.uint8)
+    else:
+        raw = rng.integers(1, 33, size=(Hb, Wb)) - 1
+        cxb = np.vectorize(lambda s: BLOCKS[int(s)][0])(smap)
+        cyb = np.vectorize(lambda s: BLOCKS[int(s)][1])(smap)
+        ty = (np.arange(Hb)[:, None] // cyb) * cyb
+        tx = (np.arange(Wb)[None, :] // cxb) * cxb
+        qf = raw[ty, tx].astype(np.uint8)
+
+    sharp = rng.integers(0, 8, size=(Hb, Wb)).astype(np.uint8)
+
+    Wt, Ht = (W + 63) // 64, (H + 63) // 64
+    if cfl_zero:
+        kx = np.zeros((Ht, Wt), np.float32)
+        kb = np.zeros((Ht, Wt), np.float32)
+        dc_cfl = dict(kx_dc=0.0, kb_dc=0.0)
+    else:
+        kx = rng.uniform(-1.0, 1.0, size=(Ht, Wt)).astype(np.float32)
+        kb = rng.uniform(-1.0, 1.0, size=(Ht, Wt)).astype(np.float32)
+        dc_cfl = dict(kx_dc=0.0, kb_dc=0.935669)  # x/b_factor_dc = 128
+
+    params = dict(BASE_PARAMS)
+    params.update(dc_cfl)
+    params.update(epf_iters=epf_iters, gab=gab)
+    return dict(name=name, xsize=W, ysize=H, ac=ac, dc=dc, strategy=smap, qf=qf,
+                sharpness=sharp, cfl_kx=kx, cfl_kb=kb, params=params,
+                out_format=out_format)
+
+
+def c1():
+    return frame(256, 256, seed=0, choices=[DCT8], qf_const=8, cfl_zero=True,
+                 epf_iters=0, gab=1, name="c1_256x256_dct8")
+
+
+def c2():
+    return frame(2048, 2048, seed=2, epf_iters=2, gab=1, name="c2_2048x2048_mixed_epf2")
+
+
+def c3():
+    return frame(4096, 4096, seed=3, p_dct32=0.5, epf_iters=2, gab=1,
+                 name="c3_4096x4096_half_dct32")
+
+
+def small(W=96, H=72, seed=11, epf_iters=2, **kw):
+    """The c2 recipe at a size the oracle finishes in well under a second."""
+    return frame(W, H, seed=seed, epf_iters=epf_iters, name=f"small_{W}x{H}", **kw)
+
+
+def c4_sizes(seed=4, n=64):
+    rng = np.random.default_rng(seed)
+    lo, hi = math.log(256), math.log(3072)
+    sides = np.exp(rng.uniform(lo, hi, size=(n, 2)))
+    sides = np.clip(np.round(sides / 8) * 8, 256, 3072).astype(int)
+    return [(int(w), int(h)) for w, h in sides]
+
+
+def c4(n=64, seed=4):
+    return [frame(w, h, seed=seed * 1000 + i, epf_iters=1, gab=1, out_format=1,
+                  name=f"c4_{i}_{w}x{h}") for i, (w, h) in enumerate(c4_sizes(seed, n))]

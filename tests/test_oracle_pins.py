@@ -1,0 +1,715 @@
+"""Pins of the FP64 oracle against facts other than itself.
+
+Each test checks an oracle function against something the draft or
+mathematics fixes independently: the draft's own 8-point butterflies and the
+recursive generator of its electronic insert (evaluated here as linear maps),
+forward/inverse round trips taken from separate clauses, closed forms,
+library routines (matrix inverse, reflecting correlation), brute-force sums on
+tiny inputs, and invariants.  None of these tests needs a GPU.
+"""
+import math
+
+import numpy as np
+import pytest
+import scipy.ndimage as ndi
+
+from oracle import oracle as O
+
+DCT_FAMILY = [0, 4, 5, 6, 7, 8, 9, 10, 11]
+EIGHT_CLASS = [1, 2, 3]
+
+
+# --------------------------------------------------------------------------
+# The draft's 1-D transforms evaluated as linear maps
+# --------------------------------------------------------------------------
+
+def butterfly8_inverse(a):
+    """I.2.1 inverse 8-point flow graph, applied to the rows of `a` (8 x m),
+    arranged as an even half (inputs 0, 2, 4, 6) and an odd half (1, 3, 5, 7)
+    whose outputs are added and subtracted symmetrically."""
+    r2 = math.sqrt(2.0)
+    c38 = math.cos(3 * math.pi / 8)
+    a0, a1, a2, a3, a4, a5, a6, a7 = a
+    # even half
+    s04, d04 = a0 + a4, a0 - a4
+    s62, d62 = a6 + a2, a6 - a2
+    rot = r2 * d62 + s62
+    even = [s04 + s62, d04 - rot, d04 + rot, s04 - s62]
+    # odd half
+    s71, d71 = a7 + a1, a7 - a1
+    s53, d53 = a5 + a3, a5 - a3
+    u = s71 + s53
+    v = s71 - s53
+    w = 2 * c38 * (d53 - d71)
+    p = d71 / c38 + w
+    q = 2 * r2 * c38 * d53 + w
+    oa = u + p
+    ob = r2 * v + oa
+    odd = [u, -oa, ob, q - ob]
+    out = [None] * 8
+    for n in range(4):
+        out[n] = even[n] + odd[n]
+        out[7 - n] = even[n] - odd[n]
+    return np.array(out)
+
+
+def butterfly8_forward(x):
+    """I.2.1 forward 8-point flow graph on the rows of `x` (8 x m), arranged
+    as symmetric sums s_j = x_j + x_{7-j} (even outputs) and differences
+    d_j = x_j - x_{7-j} (odd outputs)."""
+    c1 = 1 / math.sqrt(2.0)
+    c38 = math.cos(3 * math.pi / 8)
+    s = [x[j] + x[7 - j] for j in range(4)]
+    d = [x[j] - x[7 - j] for j in range(4)]
+    out = [None] * 8
+    out[0] = (s[0] + s[3]) + (s[1] + s[2])
+    out[4] = (s[0] + s[3]) - (s[1] + s[2])
+    e = c1 * ((s[1] - s[2]) + (s[0] - s[3]))
+    out[2] = (s[0] - s[3]) + e
+    out[6] = (s[0] - s[3]) - e
+    m12 = c1 * (d[1] + d[2])
+    h = c38 * ((d[2] + d[3]) - (d[0] + d[1]))
+    f = (d[0] + d[1]) / (2 * c38) + h
+    g = math.sqrt(2.0) * c38 * (d[2] + d[3]) + h
+    out[1] = (d[0] + m12) + f
+    out[7] = (d[0] + m12) - f
+    out[3] = (d[0] - m12) - g
+    out[5] = (d[0] - m12) + g
+    return np.array(out)
+
+
+class Generator:
+    """The Vashkevich-Petrovsky recursion of the DCT-II/III generator insert
+    (Annex R), evaluated numerically on arrays of shape (n, m) instead of
+    emitting code.  N is the transform size the constants refer to."""
+
+    def __init__(self, N):
+        self.N = N
+
+    @staticmethod
+    def even_first(n):
+        # the "P" permutation: even indices, then odd indices
+        return list(range(0, n, 2)) + list(range(1, n, 2))
+
+    @staticmethod
+    def inverse_perm(p):
+        q = [0] * len(p)
+        for i, v in enumerate(p):
+            q[v] = i
+        return q
+
+    @staticmethod
+    def quad_order(n):
+        # the "P4" permutation: index 0, then pairs taken alternately from the
+        # second half and the first half, then the last first-half index
+        if n <= 2:
+            return list(range(n))
+        half = n // 2
+        seq = [0]
+        top, bot, from_bottom = 1, 0, True
+        while len(seq) < n - 1:
+            if from_bottom:
+                seq += [half + bot, half + bot + 1]
+                bot += 2
+            else:
+                seq += [top, top + 1]
+                top += 2
+            from_bottom = not from_bottom
+        seq.append(top)
+        return seq
+
+    def c2(self, r):
+        return 2.0 * math.cos(r * math.pi / (2.0 * self.N))
+
+    # forward
+    def fwd(self, x):
+        n = x.shape[0]
+        if n == 1:
+            return x
+        h = n // 2
+        top, bot = x[:h], x[h:][::-1]
+        y_top, y_bot = top + bot, top - bot
+        z = np.concatenate([self.fwd(y_top), self.fwd_odd(y_bot, self.N // 2)])
+        out = np.empty_like(z)
+        out[self.even_first(n)] = z
+        return out
+
+    def fwd_odd(self, x, r):
+        n = x.shape[0]
+        if n == 1:
+            return x
+        h = n // 2
+        top, bot = x[:h], x[h:]
+        t = top - bot[::-1]
+        b = bot * self.c2(r)
+        y = np.concatenate([t + b, t - b])
+        z = np.concatenate([self.fwd_odd(y[:h], r // 2), self.fwd_odd(y[h:], self.N - r // 2)])
+        return z[self.quad_order(n)]
+
+    # inverse
+    def inv(self, x):
+        n = x.shape[0]
+        if n == 1:
+            return x
+        h = n // 2
+        xp = x[self.even_first(n)]
+        e = self.inv(xp[:h])
+        o = self.inv_odd(xp[h:], self.N // 2)
+        return np.concatenate([e + o, (e - o)[::-1]])
+
+    def inv_odd(self, x, r):
+        n = x.shape[0]
+        if n == 1:
+            return x
+        h = n // 2
+        xp = x[self.inverse_perm(self.quad_order(n))]
+        y = np.concatenate([self.inv_odd(xp[:h], r // 2), self.inv_odd(xp[h:], self.N - r // 2)])
+        t = y[:h] + y[h:]
+        b = (y[:h] - y[h:]) / self.c2(r)
+        return np.concatenate([t + b[::-1], b])
+
+
+def draft_inverse_matrix(N):
+    if N == 8:
+        return butterfly8_inverse(np.eye(8))
+    return Generator(N).inv(np.eye(N))
+
+
+def draft_forward_matrix(N):
+    if N == 8:
+        return butterfly8_forward(np.eye(8))
+    return Generator(N).fwd(np.eye(N))
+
+
+@pytest.mark.parametrize("N", [2, 4, 8, 16, 32])
+def test_inverse_matrix_matches_draft_transform(N):
+    # I.2.1 butterfly (N = 8) and the Annex R recursion (other N)
+    np.testing.assert_allclose(O.idct_matrix(N), draft_inverse_matrix(N), atol=1e-12, rtol=0)
+
+
+@pytest.mark.parametrize("N", [2, 4, 8, 16, 32])
+def test_forward_matrix_matches_draft_transform(N):
+    np.testing.assert_allclose(O.fdct_matrix(N), draft_forward_matrix(N), atol=1e-12, rtol=0)
+
+
+@pytest.mark.parametrize("N", [1, 2, 4, 8, 16, 32])
+def test_inverse_times_forward_is_N(N):
+    np.testing.assert_allclose(O.idct_matrix(N) @ O.fdct_matrix(N), N * np.eye(N), atol=1e-12)
+
+
+def test_generator_at_8_differs_from_butterfly_only_by_column_scale():
+    # The draft uses the explicit butterfly at N = 8; the generator would give
+    # the same DCT-III with other per-column scales.
+    g = Generator(8).inv(np.eye(8))
+    b = butterfly8_inverse(np.eye(8))
+    ratio = g[0] / b[0]
+    np.testing.assert_allclose(g, b * ratio[None, :], atol=1e-12)
+
+
+@pytest.mark.parametrize("N", [1, 2, 4, 8, 16, 32])
+def test_scale_I_makes_transform_orthonormal(N):
+    # I.2.6.1: T_N diag(I(N, u)) is the orthonormal DCT-III (pins I and D).
+    Q = O.idct_matrix(N) @ np.diag([O.scale_I(N, u) for u in range(N)])
+    np.testing.assert_allclose(Q.T @ Q, np.eye(N), atol=1e-12)
+    ref = np.array([[math.sqrt((1 if k == 0 else 2) / N) *
+                     math.cos(math.pi * (2 * n + 1) * k / (2 * N)) for k in range(N)]
+                    for n in range(N)])
+    np.testing.assert_allclose(Q, ref, atol=1e-12)
+    for u in range(N):
+        assert O.scale_I(N, u) * O.scale_D(N, u) == pytest.approx(1.0 / N, rel=1e-13)
+
+
+def test_scalef_reciprocal_pairs():
+    # ScaleF(N, n, x) * ScaleF(n, N, x) = 1 for the pairs I.2.6 and I.2.7 use.
+    for big in (8, 16, 32):
+        for small in (1, 2, 4):
+            for x in range(small):
+                assert O.scalef(big, small, x) * O.scalef(small, big, x) == pytest.approx(1.0, rel=1e-12)
+
+
+# --------------------------------------------------------------------------
+# 2-D transforms per varblock type
+# --------------------------------------------------------------------------
+
+def _rng(seed=0):
+    return np.random.default_rng(seed)
+
+
+@pytest.mark.parametrize("s", DCT_FAMILY)
+def test_dct_family_is_direct_cosine_sum(s):
+    # Brute force: every output sample as a double sum over coefficients,
+    # with the 1-D maps taken from the draft's butterfly/generator.
+    bx, by = O.varblock_size(s)
+    K = _rng(s).standard_normal((by, bx))
+    Tx, Ty = draft_inverse_matrix(bx), draft_inverse_matrix(by)
+    S = O.inverse_transform(s, K)
+    ref = np.zeros((by, bx))
+    for n in range(by):
+        for m in range(bx):
+            acc = 0.0
+            for k in range(by):
+                for l in range(bx):
+                    acc += K[k, l] * Ty[n, k] * Tx[m, l]
+            ref[n, m] = acc
+    np.testing.assert_allclose(S, ref, atol=1e-11)
+
+
+@pytest.mark.parametrize("s,gain", [(0, 64), (4, 256), (5, 1024), (6, 128), (7, 128), (8, 256),
+                                    (9, 256), (10, 512), (11, 512), (1, 1), (2, 1), (3, 16)])
+def test_round_trip_forward_then_inverse(s, gain):
+    # I.2.3 (forward) followed by I.2.4 (inverse): a multiple of the identity.
+    bx, by = O.varblock_size(s)
+    X = _rng(100 + s).standard_normal((by, bx))
+    np.testing.assert_allclose(O.inverse_transform(s, O.forward_transform(s, X)), gain * X,
+                               atol=1e-11 * gain)
+
+
+@pytest.mark.parametrize("s", EIGHT_CLASS)
+def test_eight_class_inverse_is_inverse_of_forward_map(s):
+    # The inverse map equals numpy's inverse of the forward map (times the gain).
+    gain = {1: 1.0, 2: 1.0, 3: 16.0}[s]
+    F = np.stack([O.forward_transform(s, e.reshape(8, 8)).ravel() for e in np.eye(64)], axis=1)
+    G = np.stack([O.inverse_transform(s, e.reshape(8, 8)).ravel() for e in np.eye(64)], axis=1)
+    np.testing.assert_allclose(G, gain * np.linalg.inv(F), atol=1e-10)
+
+
+def test_forward_of_constant_block_is_dc_only():
+    for s in DCT_FAMILY + EIGHT_CLASS:
+        bx, by = O.varblock_size(s)
+        K = O.forward_transform(s, np.full((by, bx), 3.25))
+        dc = K[0, 0]
+        K[0, 0] = 0.0
+        assert np.abs(K).max() < 1e-13 * abs(dc), s
+        assert dc == pytest.approx(3.25 * ({1: 1, 2: 1, 3: 16}.get(s, bx * by)), rel=1e-12)
+
+
+def test_identity_forward_keeps_sample_differences():
+    # I.2.3.4: away from the corner slots, coefficients are differences
+    # against sample (1, 1) of each 4 x 4 quarter.
+    # Arrays are [row][column]: coefficient (qx + 2 ix, qy + 2 iy) of quarter
+    # (qx, qy) holds sample (4 qx + ix, 4 qy + iy) minus sample (4 qx + 1, 4 qy + 1).
+    X = _rng(7).standard_normal((8, 8))
+    K = O.forward_transform(1, X)
+    assert K[2, 1] == pytest.approx(X[1, 4] - X[1, 5])  # quarter (1, 0), (ix, iy) = (0, 1)
+    assert K[5, 7] == pytest.approx(X[6, 7] - X[5, 5])  # quarter (1, 1), (ix, iy) = (3, 2)
+    # the (0, 0) difference of each quarter moves to the (1, 1) slot
+    assert K[3, 2] == pytest.approx(X[4, 0] - X[5, 1])  # quarter (0, 1)
+
+
+# --------------------------------------------------------------------------
+# LLF <-> DC (I.2.6, I.2.7)
+# --------------------------------------------------------------------------
+
+MULTI = [4, 5, 6, 7, 8, 9, 10, 11]
+
+
+@pytest.mark.parametrize("s", MULTI)
+def test_llf_from_dc_inverts_downsampling(s):
+    bx, by = O.varblock_size(s)
+    D = _rng(s).standard_normal((by // 8, bx // 8))
+    np.testing.assert_allclose(O.dc_from_llf(s, O.llf_from_dc(s, D)), D, atol=1e-12)
+
+
+@pytest.mark.parametrize("s", MULTI)
+def test_downsampling_is_box_mean_of_lf_reconstruction(s):
+    # I.2.6 equals the exact 8 x 8 means of the IDCT of the LF-only varblock.
+    bx, by = O.varblock_size(s)
+    cx, cy = bx // 8, by // 8
+    L = _rng(30 + s).standard_normal((cy, cx))
+    K = np.zeros((by, bx))
+    K[:cy, :cx] = L
+    S = O.inverse_transform(s, K)
+    means = S.reshape(cy, 8, cx, 8).mean(axis=(1, 3))
+    np.testing.assert_allclose(O.dc_from_llf(s, L), means, atol=1e-12)
+
+
+def _frame_of(s, W, H, dc, ac=None, qf=1, kx=0.0, kb=0.0):
+    Wb, Hb = (W + 7) // 8, (H + 7) // 8
+    Wt, Ht = (W + 63) // 64, (H + 63) // 64
+    return dict(ac=np.zeros((3, 8 * Hb, 8 * Wb), np.int32) if ac is None else ac,
+                dc=dc.astype(np.int32), strategy=np.full((Hb, Wb), s, np.uint8),
+                qf=np.full((Hb, Wb), qf - 1, np.uint8),
+                sharpness=np.zeros((Hb, Wb), np.uint8),
+                cfl_kx=np.full((Ht, Wt), kx, np.float32), cfl_kb=np.full((Ht, Wt), kb, np.float32))
+
+
+@pytest.mark.parametrize("s", DCT_FAMILY + EIGHT_CLASS)
+def test_dc_only_varblock_decodes_to_constant(s):
+    bx, by = O.varblock_size(s)
+    W, H = 2 * bx, 2 * by
+    Wb, Hb = W // 8, H // 8
+    # the same DC value in every block of a varblock, different per varblock
+    vals = np.array([[5, -17], [123, -512]])
+    dc = np.zeros((3, Hb, Wb))
+    for c in range(3):
+        dc[c] = np.kron(vals * (c + 1) // 2, np.ones((by // 8, bx // 8)))
+    # DC chroma from luma (Annex G with the DC factors): X += kX_dc * Y,
+    # B += kB_dc * Y, all constant per varblock.
+    p = O.params(W, H, dc_mul=(0.5, 0.25, 0.125), kx_dc=0.25, kb_dc=0.875)
+    xyb = O.reconstruct(p, _frame_of(s, W, H, dc))
+    d = [np.kron(vals * (c + 1) // 2, np.ones((by, bx))) * p.dc_mul[c] for c in range(3)]
+    np.testing.assert_allclose(xyb[1], d[1], atol=1e-12)
+    np.testing.assert_allclose(xyb[0], d[0] + 0.25 * d[1], atol=1e-12)
+    np.testing.assert_allclose(xyb[2], d[2] + 0.875 * d[1], atol=1e-12)
+
+
+@pytest.mark.parametrize("s", DCT_FAMILY)
+def test_lf_only_reconstruction_has_dc_as_block_means(s):
+    bx, by = O.varblock_size(s)
+    W, H = 2 * bx, 2 * by
+    Wb, Hb = W // 8, H // 8
+    dc = _rng(s).integers(-512, 513, size=(3, Hb, Wb))
+    p = O.params(W, H, dc_mul=(1.0, 1.0, 1.0), kx_dc=0.0, kb_dc=0.0)
+    xyb = O.reconstruct(p, _frame_of(s, W, H, dc))
+    means = xyb.reshape(3, Hb, 8, Wb, 8).mean(axis=(2, 4))
+    np.testing.assert_allclose(means, dc, atol=1e-10)
+
+
+def test_cropping_keeps_top_left_samples():
+    W, H = 21, 13
+    dc = _rng(3).integers(-512, 513, size=(3, 2, 3))
+    p = O.params(W, H, dc_mul=(1.0, 1.0, 1.0), kx_dc=0.0, kb_dc=0.0)
+    xyb = O.reconstruct(p, _frame_of(0, W, H, dc))
+    assert xyb.shape == (3, H, W)
+    np.testing.assert_allclose(xyb[:, 8:13, 16:21], np.broadcast_to(dc[:, 1:2, 2:3], (3, 5, 5)))
+
+
+# --------------------------------------------------------------------------
+# Dequantization (F.3, C.6.1) and chroma from luma (Annex G)
+# --------------------------------------------------------------------------
+
+def test_dequant_matrices_positive_and_symmetric():
+    for s in range(12):
+        bx, by = O.varblock_size(s)
+        for c in range(3):
+            m = O.dequant_matrix(s, c)
+            assert np.all(np.isfinite(m.ravel()[1:])) and np.all(m.ravel()[1:] > 0)
+            if bx == by:
+                np.testing.assert_allclose(m, m.T, rtol=1e-13)
+    for a, b in [(6, 7), (8, 9), (10, 11)]:
+        for c in range(3):
+            np.testing.assert_allclose(O.dequant_matrix(a, c), O.dequant_matrix(b, c).T, rtol=1e-13)
+
+
+def test_dequant_dct16_at_band_point():
+    # DCT16, position (8, 8): distance sqrt(1/2), i.e. exactly band 3 of 7;
+    # eccentricity 0, multiplier 1; numerator I(16, 8)^2 / 256 with
+    # I(16, 8) = 1 / (16 * sqrt(2/16) * cos(pi/4)) = 1/4.
+    db_y = [0.77917081615440487, -0.57424582104194355, -0.90745813428471001,
+            -0.64925837484843441]
+    band = db_y[0]
+    for v in db_y[1:]:
+        band *= (v + 1) if v > 0 else 1 / (1 - v)
+    expect = (0.25 * 0.25 / 256) / band
+    assert O.dequant_matrix(4, 1)[8, 8] == pytest.approx(expect, rel=1e-12)
+
+
+def test_dequant_dct8_on_axis_last_band():
+    # DCT8 X channel at (4, 0): distance 1/2, scaled position 5/(2 sqrt 2);
+    # interpolated geometrically between bands 1 and 2; eccentricity 1 gives
+    # the last eccentricity band, all factors 1.
+    db = [5.0, 0.0, -0.4, -0.4, -0.4, -2.0]
+    bands = [db[0]]
+    for v in db[1:]:
+        bands.append(bands[-1] * ((v + 1) if v > 0 else 1 / (1 - v)))
+    pos = 0.5 * 5 / math.sqrt(2)
+    i = int(math.floor(pos))
+    w = bands[i] * (bands[i + 1] / bands[i]) ** (pos - i)
+    I8 = lambda u: math.sqrt(2 / 8) * (math.sqrt(0.5) if u == 0 else 1) * math.cos(u * math.pi / 16)
+    expect = I8(4) * I8(0) / 64 / w
+    assert O.dequant_matrix(0, 0)[0, 4] == pytest.approx(expect, rel=1e-12)
+
+
+def test_ac_dequant_bias_and_cfl_linearity():
+    # One DCT8 varblock with a single Y coefficient q: X gets kX times the Y
+    # image, B gets kB times it (Annex G), and the Y amplitude follows the
+    # F.3 bias rule.
+    W = H = 8
+    for q, qb in [(1, 1 - 0.07005449891748593), (-1, -(1 - 0.07005449891748593)),
+                  (3, 3 - 0.145 / 3), (-5, -5 + 0.145 / 5)]:
+        ac = np.zeros((3, 8, 8), np.int32)
+        ac[1, 2, 3] = q
+        kx, kb = 0.375, -0.625
+        p = O.params(W, H, global_scale=16384, kx_dc=0.0, kb_dc=0.0)
+        f = _frame_of(0, W, H, np.zeros((3, 1, 1)), ac=ac, qf=2, kx=kx, kb=kb)
+        xyb = O.reconstruct(p, f)
+        acmul = 65536 / (16384 * 2)
+        K = np.zeros((8, 8))
+        K[2, 3] = qb * acmul * O.dequant_matrix(0, 1)[2, 3]
+        np.testing.assert_allclose(xyb[1], O.inverse_transform(0, K), atol=1e-14)
+        np.testing.assert_allclose(xyb[0], kx * xyb[1], atol=1e-14)
+        np.testing.assert_allclose(xyb[2], kb * xyb[1], atol=1e-14)
+
+
+def test_ill_formed_maps_are_rejected():
+    W = H = 32
+    p = O.params(W, H)
+    dc = np.zeros((3, 4, 4))
+    f = _frame_of(0, W, H, dc)
+    f["strategy"][0, 1] = 4  # DCT16 at an odd block column: not aligned
+    with pytest.raises(O.OracleError):
+        O.reconstruct(p, f)
+    f = _frame_of(0, 24, 32, np.zeros((3, 4, 3)))
+    f["strategy"][0, 0] = 5  # DCT32 needs 4 block columns, the frame has 3
+    with pytest.raises(O.OracleError):
+        O.reconstruct(O.params(24, 32), f)
+    f = _frame_of(0, 24, 24, np.zeros((3, 3, 3)))
+    f["strategy"][2, 2] = 4  # aligned but out of bounds
+    with pytest.raises(O.OracleError):
+        O.reconstruct(O.params(24, 24), f)
+    f = _frame_of(0, W, H, dc)
+    f["strategy"][0, 1] = 7  # DCT8x16 covering (1,0),(1,1)
+    f["strategy"][1, 0] = 6  # DCT16x8 at (0,1) would cover (1,1) again
+    with pytest.raises(O.OracleError):
+        O.reconstruct(p, f)
+    f = _frame_of(0, W, H, dc)
+    f["strategy"][0, 0] = 14  # AFV: not reconstructed by this oracle
+    with pytest.raises(O.OracleError):
+        O.reconstruct(p, f)
+
+
+# --------------------------------------------------------------------------
+# Gaborish (J.4)
+# --------------------------------------------------------------------------
+
+def test_gaborish_matches_reflecting_correlation():
+    W, H = 19, 11
+    p = O.params(W, H)
+    x = _rng(5).standard_normal((3, H, W))
+    out = O.gaborish(p, x)
+    for c in range(3):
+        w1, w2 = p.gab_w1[c], p.gab_w2[c]
+        k = np.array([[w2, w1, w2], [w1, 1.0, w1], [w2, w1, w2]])
+        k /= k.sum()
+        np.testing.assert_allclose(out[c], ndi.correlate(x[c], k, mode="reflect"), atol=1e-13)
+
+
+def test_gaborish_normalized_weights_and_constant_invariance():
+    p = O.params(5, 5)
+    x = np.zeros((3, 5, 5))
+    x[:, 2, 2] = 1.0
+    out = O.gaborish(p, x)
+    norm = 1 + 4 * 0.115169525 + 4 * 0.061248592
+    assert out[1, 2, 2] == pytest.approx(1 / norm, rel=1e-13)
+    assert out[1, 2, 1] == pytest.approx(0.115169525 / norm, rel=1e-13)
+    assert out[1, 1, 1] == pytest.approx(0.061248592 / norm, rel=1e-13)
+    np.testing.assert_allclose(O.gaborish(p, np.full((3, 5, 5), 0.7)), 0.7, atol=1e-15)
+
+
+# --------------------------------------------------------------------------
+# Edge-preserving filter (J.2)
+# --------------------------------------------------------------------------
+
+def test_weight_closed_form_values():
+    # sad = 0 gives high16 = 127 << 7, i.e. exactly 1.0 (the centre weight).
+    assert O.epf_weight(0, -8128) == 1.0
+    # (min(sad, 507) << 6) * mul >> 16 = -128 moves the exponent down by one.
+    assert O.epf_weight(16, -8192) == 0.5
+    # saturation at sad 507
+    assert O.epf_weight(507, -1000) == O.epf_weight(9999, -1000)
+
+
+def test_mul_table_brackets_one_half():
+    t = O.mul_table(0)
+    for sigma in range(16, 673, 4):
+        m = t[sigma]
+        assert O.epf_weight(sigma, m) > 0.5
+        assert O.epf_weight(sigma, m - 1) <= 0.5
+    # interpolated entries lie between their neighbours, steps truncated
+    for sigma in range(16, 672, 4):
+        step = int((t[sigma + 4] - t[sigma]) / 4)
+        for i in range(1, 4):
+            assert t[sigma + i] == t[sigma] + i * step
+    assert np.all(np.diff(t[16:]) >= 0)
+
+
+def _epf_frame(W, H, qf=4, sharp=7):
+    Wb, Hb = (W + 7) // 8, (H + 7) // 8
+    return dict(strategy=np.zeros((Hb, Wb), np.uint8), qf=np.full((Hb, Wb), qf - 1, np.uint8),
+                sharpness=np.full((Hb, Wb), sharp, np.uint8))
+
+
+def test_epf_constant_image_is_invariant():
+    W, H = 24, 16
+    p = O.params(W, H, global_scale=32768)
+    x = np.stack([np.full((H, W), v) for v in (0.01, 0.4, 0.3)])
+    np.testing.assert_allclose(O.epf_pass(p, _epf_frame(W, H), x), x, atol=1e-15)
+
+
+def _step_case(vertical, strong):
+    W = H = 32
+    e = 20  # edge inside block column (or row) 2
+    a = np.array([0.01, 0.30, 0.20])
+    # strong: weights across the edge fall below the threshold; weak: guide
+    # steps of 2, 2, 0 so that one, two and three crossed patch columns give
+    # distinct surviving weights
+    b = np.array([0.05, 0.80, 0.60]) if strong else np.array([0.012, 0.32, 0.21])
+    x = np.empty((3, H, W))
+    for c in range(3):
+        if vertical:
+            x[c] = np.where(np.arange(W)[None, :] >= e, b[c], a[c])
+        else:
+            x[c] = np.where(np.arange(H)[:, None] >= e, b[c], a[c])
+    p = O.params(W, H, global_scale=32768)  # quant * quant_mul = 32768*4/65536*20 = 40
+    return p, x, e, a, b
+
+
+@pytest.mark.parametrize("vertical", [True, False])
+@pytest.mark.parametrize("strong", [True, False])
+def test_epf_step_edge_closed_form(vertical, strong):
+    p, x, e, a, b = _step_case(vertical, strong)
+    out, guide, sigma = O.epf_pass(p, _epf_frame(32, 32), x, want_debug=True)
+    # guide bytes on both sides
+    im3 = (5 * 50 / 250) ** (1 / 3)
+    mins = np.array([-0.03 * im3, 0, 0])
+    scale = np.array([p.epf_scale[0], p.epf_scale[1], p.epf_scale[2]])
+    gl = np.floor(np.clip(((a - mins) * scale).astype(np.float32), 0, 255))
+    gr = np.floor(np.clip(((b - mins) * scale).astype(np.float32), 0, 255))
+    delta = int(np.abs(gl - gr).sum())
+    # sigma: only the blocks holding the edge have a range, the largest
+    # channel step of `scaled`; there sigma = trunc(min(range * 12.6 * 1, 40, 170))
+    rng_edge = np.max(np.abs(b - a) * scale)
+    sig = int(min(rng_edge * 12.6, 40.0, 170.0))
+    assert sig >= 16
+    for blk in range(4):
+        for other in range(4):
+            bxy = (other, blk) if vertical else (blk, other)
+            assert sigma[bxy] == (sig if blk == 2 else 0)
+    mul = O.mul_table()[sig]
+    side = lambda u: u >= e
+    for t in range(32):  # coordinate across the edge
+        if t // 8 != 2:
+            continue
+        # patch extent across the edge: 4 samples horizontally, 3 vertically;
+        # window offsets -3..4 horizontally, -3..3 vertically
+        ext = range(-1, 3) if vertical else range(-1, 2)
+        win = range(-3, 5) if vertical else range(-3, 4)
+        rep = 3 if vertical else 4  # patch size along the edge
+        cnt_along = 7 if vertical else 8  # window size along the edge
+        wsum = np.zeros(3)
+        sw = 0.0
+        for o in win:
+            k = sum(side(t + i) != side(t + o + i) for i in ext)
+            w = O.epf_weight(rep * delta * k, mul)
+            if w < 0.3:
+                w = 0.0
+            v = b if side(t + o) else a
+            wsum += cnt_along * w * v
+            sw += cnt_along * w
+        expect = wsum / sw
+        got = out[:, :, t].T if vertical else out[:, t, :].T
+        np.testing.assert_allclose(got, np.broadcast_to(expect, (32, 3)), atol=1e-13)
+    # pixels outside the edge blocks are unchanged
+    mask = np.ones(32, bool)
+    mask[16:24] = False
+    if vertical:
+        np.testing.assert_array_equal(out[:, :, mask], x[:, :, mask])
+    else:
+        np.testing.assert_array_equal(out[:, mask, :], x[:, mask, :])
+
+
+def test_epf_guide_bytes_golden():
+    # J.2.2 with the C.10 scales and target_nits_div50 = 5 (so the intensity
+    # multiplier is 1): g = floor(clamp((in - min) * scale, 0, 255)),
+    # min = (-0.03, 0, 0).  0.03 * 899.676941 = 26.99..., 0.28 * 899.676941 =
+    # 251.90..., 1 * 111.965157, 2 * 45.275791 = 90.55...
+    cases = [((0.0, 1.0, 2.0), (26, 111, 90)), ((0.25, 0.0, -0.1), (251, 0, 0)),
+             ((0.3, 2.5, 6.0), (255, 255, 255)), ((-0.05, 0.5, 0.5), (0, 55, 22))]
+    W, H = 8, 8
+    p = O.params(W, H, global_scale=32768)
+    for vals, expect in cases:
+        x = np.stack([np.full((H, W), v) for v in vals])
+        _, guide, _ = O.epf_pass(p, _epf_frame(W, H), x, want_debug=True)
+        assert tuple(int(guide[c, 3, 3]) for c in range(3)) == expect
+
+
+def test_epf_commutes_with_vertical_flip():
+    W, H = 40, 32
+    r = _rng(9)
+    x = np.stack([0.02 * r.standard_normal((H, W)), 0.4 + 0.2 * r.standard_normal((H, W)),
+                  0.3 + 0.2 * r.standard_normal((H, W))])
+    f = _epf_frame(W, H)
+    f["sharpness"] = r.integers(0, 8, size=f["sharpness"].shape).astype(np.uint8)
+    f["qf"] = r.integers(0, 32, size=f["qf"].shape).astype(np.uint8)
+    p = O.params(W, H, global_scale=32768)
+    out = O.epf_pass(p, f, x)
+    ff = {k: np.ascontiguousarray(v[::-1]) for k, v in f.items()}
+    out_f = O.epf_pass(p, ff, np.ascontiguousarray(x[:, ::-1]))
+    np.testing.assert_allclose(out_f[:, ::-1], out, atol=1e-12)
+    assert np.abs(out - x).max() > 1e-3  # the filter did act
+
+
+def test_epf_low_sigma_and_thresholded_weights_pass_through():
+    W, H = 16, 16
+    r = _rng(4)
+    x = np.stack([0.02 * r.standard_normal((H, W)), 0.4 + 0.3 * r.standard_normal((H, W)),
+                  0.3 + 0.3 * r.standard_normal((H, W))])
+    p = O.params(W, H, global_scale=32768)
+    f = _epf_frame(W, H, qf=1)  # quant * 20 = 10 < 16
+    np.testing.assert_array_equal(O.epf_pass(p, f, x), x)
+    f = _epf_frame(W, H, sharp=0)  # sharpness LUT entry 0
+    np.testing.assert_array_equal(O.epf_pass(p, f, x), x)
+    # weight 1.0 needs sad 0: with this threshold only identical patches count
+    p = O.params(W, H, global_scale=32768, epf_weight_min=1.0)
+    np.testing.assert_array_equal(O.epf_pass(p, _epf_frame(W, H), x), x)
+    with pytest.raises(O.OracleError):  # the centre weight 1.0 must survive
+        O.epf_pass(O.params(W, H, epf_weight_min=1.5), _epf_frame(W, H), x)
+
+
+# --------------------------------------------------------------------------
+# XYB -> RGB (L.2) and output quantization
+# --------------------------------------------------------------------------
+
+def _xyb_from_rgb(p, rgb):
+    """Forward opsin transform, inverting the L.2 steps with numpy's matrix
+    inverse: RGB -> mix -> gamma -> (X, Y, B)."""
+    M = np.array(p.opsin_inv[:]).reshape(3, 3)
+    bias = np.array(p.opsin_bias[:])
+    mix = np.linalg.solve(M, rgb.reshape(3, -1)).reshape(rgb.shape)
+    g = np.cbrt(mix - bias.reshape(3, 1, 1))
+    return np.stack([(g[0] - g[1]) / 2, (g[0] + g[1]) / 2, g[2]])
+
+
+def test_xyb_round_trip_known_colours():
+    p = O.params(4, 2)
+    cols = np.array([[255, 255, 255], [0, 0, 0], [128, 128, 128], [255, 0, 0],
+                     [0, 255, 0], [0, 0, 255], [30, 200, 90], [250, 5, 180]], float)
+    rgb = cols.T.reshape(3, 2, 4)
+    xyb = _xyb_from_rgb(p, rgb)
+    np.testing.assert_allclose(O.xyb_to_rgb(p, xyb), rgb / 255.0, atol=1e-12)
+
+
+def test_grey_has_no_x_and_the_default_b_to_y_ratio():
+    # Grey maps to X = 0, and B / Y of white is the default kB of Annex G
+    # (0.935669); the opsin biases pull darker greys slightly above it.
+    p = O.params(3, 1)
+    rgb = np.array([[[50.0, 128.0, 255.0]]] * 3)
+    xyb = _xyb_from_rgb(p, rgb)
+    assert np.abs(xyb[0]).max() < 1e-6
+    ratio = (xyb[2] / xyb[1]).ravel()
+    assert abs(ratio[2] - 0.935669) < 5e-5
+    assert np.all(np.diff(ratio) < 0) and ratio[0] - 0.935669 < 3e-4
+
+
+def test_target_nits_scales_output():
+    p5 = O.params(2, 1)
+    p20 = O.params(2, 1, target_nits_div50=20)
+    xyb = np.array([[[0.01, -0.02]], [[0.5, 0.7]], [[0.4, 0.6]]])
+    np.testing.assert_allclose(O.xyb_to_rgb(p20, xyb) * 4, O.xyb_to_rgb(p5, xyb), rtol=1e-13)
+
+
+@pytest.mark.parametrize("bits", [8, 16])
+def test_quantize_codes_at_rounding_boundaries(bits):
+    maxv = (1 << bits) - 1
+
+    def decode(e):  # sRGB decoding function, the inverse of the encoding
+        return np.where(e <= 0.04045, e / 12.92, ((e + 0.055) / 1.055) ** 2.4)
+
+    k = np.arange(1, maxv + 1, max(1, maxv // 997))
+    edge = decode((k - 0.5) / maxv)
+    above = O.quantize_srgb(bits, edge * (1 + 1e-9) + 1e-15)
+    below = O.quantize_srgb(bits, edge * (1 - 1e-9) - 1e-15)
+    np.testing.assert_array_equal(above, k)
+    np.testing.assert_array_equal(below, k - 1)
+    ends = O.quantize_srgb(bits, np.array([-0.5, 0.0, 1.0, 3.0]))
+    np.testing.assert_array_equal(ends, [0, 0, maxv, maxv])
