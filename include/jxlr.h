@@ -1,0 +1,196 @@
+/*
+ * jxlr.h -- JPEG XL VarDCT pixel reconstruction on MI355X (gfx950), C ABI.
+ *
+ * Implements the data-parallel part of the VarDCT decoding process of the
+ * JPEG XL Committee Draft (ISO/IEC 18181 CD, 2019-08-05): from entropy-decoded
+ * quantized coefficients to RGB samples, in the draft's stage order
+ *   F.2/F.3 dequantization -> Annex G chroma from luma -> I.2.7 LLF from DC
+ *   -> I.2.4 inverse transform selected by DctSelect (C.5.4)
+ *   -> J.2 edge-preserving filter (0..n passes) -> J.4 Gaborish
+ *   -> L.2 XYB to RGB (and optional sRGB 8/16-bit encoding).
+ * Entropy decoding (Annex D) and bitstream parsing are not part of it: the
+ * caller passes decoded header fields and sample planes.
+ *
+ * Memory: every plane pointer in jxlr_frame_io and every workspace/debug
+ * pointer is a DEVICE pointer on the context's device, owned by the caller.
+ * The library never allocates or frees inside a decode call; it allocates only
+ * its constant tables in jxlr_create and frees them in jxlr_destroy.
+ *
+ * Ordering: launches are asynchronous on the given stream (NULL = the null
+ * stream) and ordered with other work on it.  Parameter and size errors are
+ * reported synchronously, before anything is enqueued.  A DctSelect map that
+ * is ill-formed (C.5.4) is detected on the device: the affected 32 x 32 regions
+ * are written as zero and a sticky flag is set that jxlr_get_device_status
+ * reports; jxlr_validate_maps_host checks the same rules on the host first.
+ * On any error no output content is guaranteed.
+ *
+ * Threading: a context may be used from several host threads and streams at
+ * once, provided each concurrent call has its own workspace and outputs.
+ */
+#ifndef JXLR_H
+#define JXLR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  JXLR_OK = 0,
+  JXLR_E_NULL = 1,        /* a required pointer is NULL */
+  JXLR_E_SIZE = 2,        /* xsize/ysize zero or above JXLR_MAX_DIM, or a stride too small */
+  JXLR_E_STRATEGY = 3,    /* DctSelect value not in the C.5.4 table or not supported */
+  JXLR_E_ALIGN = 4,       /* varblock not naturally aligned, out of bounds or overlapping (C.5.4) */
+  JXLR_E_QUANT = 5,       /* quant field not uniform within a varblock (C.5.5) */
+  JXLR_E_DEQUANT = 6,     /* dequantization matrix entry not positive and finite (C.6.1) */
+  JXLR_E_PARAM = 7,       /* frame parameter out of range (see jxlr_frame_params) */
+  JXLR_E_WORKSPACE = 8,   /* workspace smaller than jxlr_workspace_bytes */
+  JXLR_E_HIP = 9,         /* a HIP runtime call failed */
+  JXLR_E_DEVICE_VALIDATION = 10 /* sticky: the device found an ill-formed DctSelect map */
+} jxlr_status;
+
+/* Transform types; numbering of the C.5.4 table.  This library reconstructs
+ * types 0..11 (DCT4X8, DCT8X4 and AFV are rejected with JXLR_E_STRATEGY).
+ * "DCT N x M" covers bxsize = max(8, N) by bysize = max(8, M) pixels (I.2.5):
+ * the first number is the width. */
+typedef enum {
+  JXLR_DCT8 = 0, JXLR_IDENTITY = 1, JXLR_DCT2 = 2, JXLR_DCT4 = 3, JXLR_DCT16 = 4,
+  JXLR_DCT32 = 5, JXLR_DCT16X8 = 6, JXLR_DCT8X16 = 7, JXLR_DCT32X8 = 8,
+  JXLR_DCT8X32 = 9, JXLR_DCT32X16 = 10, JXLR_DCT16X32 = 11, JXLR_DCT4X8 = 12,
+  JXLR_DCT8X4 = 13, JXLR_AFV = 14
+} jxlr_strategy;
+
+/* Output sample formats.  F32: linear RGB of L.2 divided by 255 ("[0,1]-scaled",
+ * not clamped).  U8/U16: the sRGB transfer function (IEC 61966-2-1) applied to
+ * the [0,1]-scaled value clamped to [0, 1], then floor(v * (2^b - 1) + 0.5). */
+typedef enum { JXLR_OUT_F32 = 0, JXLR_OUT_U8_SRGB = 1, JXLR_OUT_U16_SRGB = 2 } jxlr_out_format;
+
+#define JXLR_MAX_DIM 65536u
+
+/* Decoded frame-header fields.  Channel order X, Y, B.  jxlr_params_default
+ * fills the draft's defaults. */
+typedef struct {
+  uint32_t xsize, ysize;       /* frame size in pixels, 1..JXLR_MAX_DIM (A.4.2, 6.2) */
+  uint32_t global_scale;       /* global_scale_minus_1 + 1, 1..65536 (C.4.2) */
+  float    dc_mul[3];          /* mX_DC, mY_DC, mB_DC of C.4.1, already divided by
+                                  global_scale * (quant_dc_minus_1 + 1) */
+  int32_t  extra_levels[3];    /* extra_levels_xyb of C.5.2, 0..3 */
+  float    kx_dc, kb_dc;       /* DC chroma-from-luma factors as kX, kB (C.4.3, Annex G) */
+  int32_t  gab;                /* loop_filter.gab: apply Gaborish (C.10, J.4) */
+  float    gab_w1[3], gab_w2[3]; /* Gaborish edge and corner weights per channel (C.10) */
+  int32_t  epf_iters;          /* edge-preserving filter passes, 0..3; 0 = loop_filter.epf off */
+  float    epf_weight_min;     /* C.10; at most 1 */
+  float    epf_scale[3];       /* C.10 */
+  float    epf_sharp_lut[8];   /* C.10 */
+  float    epf_range_max, epf_range_mul, epf_quant_mul; /* C.10 */
+  int32_t  epf_sigma_max;      /* C.10, 0..672 */
+  int32_t  epf_sigma_shift;    /* kSigmaShift of J.2.4 (undefined by the draft), 0..8 */
+  float    opsin_inv[9];       /* inverse opsin absorbance matrix, row-major (L.2, C.4.9) */
+  float    opsin_bias[3];      /* opsin biases (L.2, C.4.9) */
+  int32_t  target_nits_div50;  /* ImageMetadata (A.4.5), >= 1 */
+  int32_t  out_format;         /* jxlr_out_format */
+} jxlr_frame_params;
+
+/* Input and output planes of one frame.  With Wb = ceil(xsize/8),
+ * Hb = ceil(ysize/8), Wt = ceil(xsize/64), Ht = ceil(ysize/64):
+ *   ac[c]      int32 [8*Hb rows][8*Wb], row stride ac_stride (elements):
+ *              quantized AC coefficients; coefficient (x, y) of the varblock
+ *              with top-left block (bx0, by0) sits at (8*bx0 + x, 8*by0 + y);
+ *              the varblock's LLF corner (x < bx/8, y < by/8) is ignored (F.2)
+ *   dc[c]      int32 [Hb][Wb], stride dc_stride: quantized DC (C.5.2, F.2)
+ *   strategy   uint8 [Hb][Wb], stride map_stride: DctSelect (C.5.4); only the
+ *              entry at each varblock's top-left block is read
+ *   qf_minus_1 uint8 [Hb][Wb], stride map_stride: quant field value dv of
+ *              C.5.5 (AcMul = 65536 / (global_scale * (1 + dv))); uniform per
+ *              varblock
+ *   sharpness  uint8 [Hb][Wb], stride map_stride: C.5.6, 0..7 (read only
+ *              when epf_iters > 0)
+ *   cfl_kx/kb  float [Ht][Wt], stride cfl_stride: kX and kB of Annex G per
+ *              64 x 64 tile (from XFromY / BFromY of C.5.3)
+ *   out[c]     [ysize][xsize] of float, uint8 or uint16 (out_format), row
+ *              stride out_stride in elements: R, G, B planes. */
+typedef struct {
+  const int32_t* ac[3];
+  size_t ac_stride;
+  const int32_t* dc[3];
+  size_t dc_stride;
+  const uint8_t* strategy;
+  const uint8_t* qf_minus_1;
+  const uint8_t* sharpness;
+  size_t map_stride;
+  const float* cfl_kx;
+  const float* cfl_kb;
+  size_t cfl_stride;
+  void* out[3];
+  size_t out_stride;
+} jxlr_frame_io;
+
+typedef struct jxlr_ctx jxlr_ctx;
+
+/* Human-readable name of a status. */
+const char* jxlr_status_string(jxlr_status s);
+
+/* Fills *p with the draft's defaults (C.4.1-C.4.3, C.10, L.2, A.4.5) for a
+ * frame of xsize x ysize: global_scale 1, DC weights {4096, 512, 256},
+ * x/b_factor_dc = 128, Gaborish on, one EPF pass, F32 output. */
+jxlr_status jxlr_params_default(jxlr_frame_params* p, uint32_t xsize, uint32_t ysize);
+
+/* Creates a context on HIP device `device`: builds the default dequantization
+ * matrices (C.6.1.1), transform matrices (I.2.1, I.2.6), LLF tables (I.2.7)
+ * and the EPF mul_table (J.2.4) on the host and uploads them. */
+jxlr_status jxlr_create(jxlr_ctx** ctx, int device);
+void jxlr_destroy(jxlr_ctx* ctx);
+
+/* Host-side check of host copies of the maps against C.5.4 (every varblock
+ * type supported, naturally aligned, inside the frame, no overlap) and C.5.5
+ * (quant field uniform within each varblock).  `sharpness` may be NULL;
+ * otherwise each entry must be <= 7. */
+jxlr_status jxlr_validate_maps_host(const jxlr_frame_params* p, const uint8_t* strategy,
+                                    const uint8_t* qf_minus_1, const uint8_t* sharpness,
+                                    size_t map_stride);
+
+/* Device workspace jxlr_decode needs for one frame: two XYB float planes sets
+ * (3 * xsize * ysize * 4 bytes each; one when epf_iters == 0), 256-byte
+ * aligned. */
+size_t jxlr_workspace_bytes(const jxlr_frame_params* p);
+
+/* The whole path for one frame: reconstruct, epf_iters EPF passes, Gaborish
+ * (if p->gab), XYB -> RGB into io->out.  ws must hold jxlr_workspace_bytes(p). */
+jxlr_status jxlr_decode(jxlr_ctx* ctx, const jxlr_frame_params* p, const jxlr_frame_io* io,
+                        void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* ---- stage entry points (the pieces jxlr_decode runs, for testing and for
+ * callers that keep XYB) --------------------------------------------------
+ * XYB planes are float [3][ysize][xsize] with row stride xyb_stride elements,
+ * plane c at xyb + c * ysize * xyb_stride. */
+
+/* F.2, F.3, Annex G, I.2.7, I.2.4 and the crop of 6.2: coefficient planes of
+ * io -> XYB samples. io->out and io->sharpness are not used. */
+jxlr_status jxlr_reconstruct(jxlr_ctx* ctx, const jxlr_frame_params* p, const jxlr_frame_io* io,
+                             float* xyb, size_t xyb_stride, hipStream_t stream);
+
+/* One edge-preserving filter pass (J.2), xyb_in -> xyb_out (distinct buffers).
+ * Uses io->strategy, qf_minus_1, sharpness.  Optional debug outputs (NULL to
+ * skip): guide bytes uint8 [3][ysize][xsize] (J.2.2) and sigma int32 [Hb][Wb]
+ * (J.2.4) of this pass. */
+jxlr_status jxlr_epf_pass(jxlr_ctx* ctx, const jxlr_frame_params* p, const jxlr_frame_io* io,
+                          const float* xyb_in, float* xyb_out, size_t xyb_stride,
+                          uint8_t* guide_dbg, int32_t* sigma_dbg, hipStream_t stream);
+
+/* Gaborish (J.4, when p->gab) and XYB -> RGB (L.2) into io->out in
+ * p->out_format. */
+jxlr_status jxlr_finish(jxlr_ctx* ctx, const jxlr_frame_params* p, const jxlr_frame_io* io,
+                        const float* xyb, size_t xyb_stride, hipStream_t stream);
+
+/* Reads and clears the sticky device-validation flag: JXLR_OK or
+ * JXLR_E_DEVICE_VALIDATION.  Synchronizes `stream`. */
+jxlr_status jxlr_get_device_status(jxlr_ctx* ctx, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,289 @@
+// Constant tables of the VarDCT reconstruction library, built on the host in
+// double precision and stored as binary32 for the kernels.
+//
+//   - inverse transform matrices (I.2.1 and the generated transforms), derived
+//     from the scale factors of I.2.6.1: T_N = Q_N diag(1 / I(N, k)) where Q_N
+//     is the orthonormal DCT-III;
+//   - LLF-from-DC factors (I.2.7.2);
+//   - default dequantization matrices (C.6.1, C.6.1.1);
+//   - the EPF mul_table (J.2.4).
+#include "jxlr_tables.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+namespace jxlr {
+namespace {
+
+constexpr double kPi = 3.141592653589793238462643383279502884;
+
+// I.2.6.1 building blocks.
+double i8(int n, int u) {
+  const double eps = u == 0 ? std::sqrt(0.5) : 1.0;
+  return std::sqrt(2.0 / n) * eps * std::cos(u * kPi / (2.0 * n));
+}
+double d8(int n, int u) { return 1.0 / (n * i8(n, u)); }
+double scale_i(int n, int u) { return n == 8 ? i8(n, u) : d8(n, u); }
+double scale_d(int n, int u) { return n == 8 ? d8(n, u) : i8(n, u); }
+// C(N, n, x): product of cos(x pi / (2 m)) for m = N, N/2, ... above n, or
+// its reciprocal when n > N.
+double scale_c(int N, int n, int x) {
+  if (n > N) return 1.0 / scale_c(n, N, x);
+  double v = 1.0;
+  for (int m = N; m > n; m /= 2) v *= std::cos(x * kPi / (2.0 * m));
+  return v;
+}
+// ScaleF(N, n, x) of I.2.6.1.
+double scale_f(int N, int n, int x) {
+  return std::sqrt(double(N) * n) * scale_d(N, x) * scale_i(n, x) * scale_c(N, n, x);
+}
+
+// Orthonormal DCT-III: q[n][k].
+double ortho(int n_size, int n, int k) {
+  const double a = std::sqrt((k == 0 ? 1.0 : 2.0) / n_size);
+  return a * std::cos(kPi * (2 * n + 1) * k / (2.0 * n_size));
+}
+
+// ------------------------------------------------------------------------
+// Dequantization encodings of C.6.1.1 (channel X, Y, B).
+struct BandSet {
+  int n;
+  double v[3][8];
+};
+
+const BandSet kDist8 = {6, {{5.0, 0.0, -0.4, -0.4, -0.4, -2.0},
+                            {1.1, 0.0, -0.3, -0.3, -0.3, -0.3},
+                            {1.0, -3.0, 0.0, 0.0, -1.0, -2.0}}};
+const BandSet kDist4 = {4, {{32.0, -0.4, 0.0, 0.0}, {6.0, 0.0, 0.0, -0.0}, {4.0, -5.0, -1.0, -1.0}}};
+const double kDct4Mul[3][2] = {{1.0, 1.0}, {0.7, 0.7}, {1.0, 1.0}};
+const BandSet kDist16 = {7,
+                         {{3.1965020925735868, -1.8000777393353804, -0.39424529824571225,
+                           -0.33909377445710343, -0.6350101832695744, -0.90177264050827612,
+                           -1.5162099239887414},
+                          {0.77917081615440487, -0.57424582104194355, -0.90745813428471001,
+                           -0.64925837484843441, -0.35865440981033403, -0.21322389111877305,
+                           -0.27615025315725483},
+                          {0.22259376988644336, -3.0531423165804414, -0.2, -0.30687130033378396,
+                           -0.42708730624733904, -1.4856834539296244, -5.9209142884401604}}};
+const BandSet kDist32 = {8,
+                         {{0.47968775359573942, -1.025, -0.98, -0.9012, -0.4, -0.48819395464,
+                           -0.421064, -0.27},
+                          {0.22295421389982905, -0.8041958212306401, -0.7633036457487539,
+                           -0.55660379990111464, -0.49785304658857626, -0.43699592683512467,
+                           -0.40180866526242109, -0.27321683125358037},
+                          {0.11607457694128877, -3.060733579805728, -2.0413270132490346,
+                           -2.0235650159727417, -0.5495389509954993, -0.4, -0.4, -0.3}}};
+const BandSet kDist16x8 = {7, {{5.0, -0.7, -0.7, -0.2, -0.2, -0.2, -0.5},
+                               {1.0, -0.5, -0.5, -0.5, -0.2, -0.2, -0.2},
+                               {0.35, -1.4, -0.2, -0.5, -0.5, -1.5, -3.6}}};
+const BandSet kDist32x8 = {8,
+                           {{0.90897201669289496, -2.523575079652864, 1.5606102630460328,
+                             -0.6828050717528521, -14.770016895841904, -31.365240527393656,
+                             0.565929254166433, 26.789646874558219},
+                            {0.3603042187746216, -0.11724474917749789, -0.85426302204085935,
+                             -0.5404181207241352, -0.45637619443533173, -0.82707923060149569,
+                             -1.09760551067614, -54.16057009483842},
+                            {0.25176400522276937, -10.060949304689093, -4.5316627381323995,
+                             -5.4569229849460807, -10.549754675878864, 1.7512906265092971,
+                             -1.6854706115725824, 3.3092762331901451}}};
+const BandSet kEcc32x8 = {4,
+                          {{-0.40751133465833289, 2.2055690721475925, -1.4434547377534228,
+                            2.0590289434445102},
+                           {0.12452072219659419, 0.065578935001406033, -0.14598888885596958,
+                            0.12114139909222557},
+                           {0.0586589025020419, -2.2654958780302183, -4.6996221931893647,
+                            1.8254498073137184}}};
+const BandSet kDist32x16 = {8,
+                            {{1.1280371559733287, -0.98868, -0.658, -0.42026, -0.22712, -0.2206,
+                              -0.226, -0.2},
+                             {0.38961075971152237, -0.62525308982767058, -0.83770786552491361,
+                              -0.79014862079498627, -0.2692727459704829, -0.38272769465388551,
+                              -0.2292422253091453, -0.20719098826199578},
+                             {0.098, -2.41, -0.23, -0.2, -0.4, -0.8, -0.4, -0.5}}};
+const double kIdentityW[3][3] = {{221.50801256717435, 7087.151589594002, 4466.9924939259863},
+                                 {29.535505378287006, 1454.6663024982124, 1368.041230099175},
+                                 {9.2887405354132238, 23.982311358829531, 11.201853748207084}};
+const double kDct2W[3][6] = {{3840.0, 2560.0, 1280.0, 640.0, 480.0, 300.0},
+                             {960.0, 640.0, 320.0, 180.0, 140.0, 120.0},
+                             {640.0, 320.0, 128.0, 64.0, 32.0, 16.0}};
+
+// Band multiplier of an encoded band value (C.6.1).
+double band_mult(double v) { return v > 0 ? 1.0 + v : 1.0 / (1.0 - v); }
+
+// Cumulative band values: element 0 is `first`, each later one multiplies in
+// the next encoded value.
+std::vector<double> cumulative(double first, const double* enc, int count) {
+  std::vector<double> out(1, first);
+  for (int i = 0; i < count; ++i) out.push_back(out.back() * band_mult(enc[i]));
+  return out;
+}
+
+// Geometric interpolation between band points; positions at or beyond the
+// last point take the last value.
+double interp(double pos, double span, const std::vector<double>& pts) {
+  const int last = int(pts.size()) - 1;
+  const double sp = pos * last / span;
+  const double fl = std::floor(sp);
+  if (fl >= last) return pts[last];
+  const int i = int(fl);
+  return pts[i] * std::pow(pts[i + 1] / pts[i], sp - fl);
+}
+
+// DCT-mode weight matrix for X columns and Y rows, row-major.
+std::vector<double> band_weights(int X, int Y, const BandSet& dist, const BandSet* ecc, int c,
+                                 int n_ecc) {
+  // distance bands: db[0], then one multiplier per further encoded value
+  std::vector<double> dpts = cumulative(dist.v[c][0], &dist.v[c][1], dist.n - 1);
+  std::vector<double> zeros(8, 0.0);
+  std::vector<double> epts = cumulative(1.0, ecc ? ecc->v[c] : zeros.data(), n_ecc);
+  std::vector<double> w(size_t(X) * Y);
+  for (int y = 0; y < Y; ++y) {
+    for (int x = 0; x < X; ++x) {
+      const double u = double(x) / X, v = double(y) / Y;
+      const double dist_v = std::hypot(u, v);
+      double m = interp(dist_v, std::sqrt(2.0), dpts);
+      if (x || y) m *= interp(std::fabs(u - v) / dist_v, 1.0, epts);
+      w[size_t(y) * X + x] = m;
+    }
+  }
+  return w;
+}
+
+}  // namespace
+
+int dq_offset(int s) {
+  int off = 0;
+  for (int t = 0; t < s; ++t) off += 3 * 64 * blocks_x(t) * blocks_y(t);
+  return off;
+}
+
+bool dequant_matrix_f64(int s, int c, double* out) {
+  const int X = 8 * blocks_x(s), Y = 8 * blocks_y(s);
+  std::vector<double> w(size_t(X) * Y, 1.0), num(size_t(X) * Y, 1.0);
+  auto at = [X](std::vector<double>& m, int x, int y) -> double& { return m[size_t(y) * X + x]; };
+  switch (s) {
+    case 1: {  // Identity mode
+      for (auto& v : w) v = kIdentityW[c][0];
+      at(w, 1, 0) = at(w, 0, 1) = kIdentityW[c][1];
+      at(w, 1, 1) = kIdentityW[c][2];
+      break;
+    }
+    case 2: {  // DCT2 mode: index by the larger and smaller coordinate
+      for (int y = 0; y < 8; ++y)
+        for (int x = 0; x < 8; ++x) {
+          const int hi = std::max(x, y), lo = std::min(x, y);
+          int k = -1;
+          if (hi == 1) k = lo;                 // (0,1)/(1,0) -> 0, (1,1) -> 1
+          else if (hi >= 2 && hi < 4) k = lo < 2 ? 2 : 3;
+          else if (hi >= 4) k = lo < 4 ? 4 : 5;
+          if (k >= 0) at(w, x, y) = kDct2W[c][k];
+        }
+      break;
+    }
+    case 3: {  // DCT4 mode: 4x4 band matrix, each entry covering 2x2
+      std::vector<double> w4 = band_weights(4, 4, kDist4, nullptr, c, 2);
+      for (int y = 0; y < 8; ++y)
+        for (int x = 0; x < 8; ++x) {
+          at(w, x, y) = w4[(y / 2) * 4 + x / 2];
+          at(num, x, y) = scale_i(4, x / 2) * scale_i(4, y / 2) / 64.0;
+        }
+      at(w, 1, 0) /= kDct4Mul[c][0];
+      at(w, 0, 1) /= kDct4Mul[c][0];
+      at(w, 1, 1) /= kDct4Mul[c][1];
+      break;
+    }
+    default: {  // DCT mode
+      const BandSet* dist = nullptr;
+      const BandSet* ecc = nullptr;
+      int n_ecc = 3;
+      switch (s) {
+        case 0: dist = &kDist8; break;
+        case 4: dist = &kDist16; break;
+        case 5: dist = &kDist32; n_ecc = 4; break;
+        case 6: case 7: dist = &kDist16x8; break;
+        case 8: case 9: dist = &kDist32x8; ecc = &kEcc32x8; n_ecc = 4; break;
+        case 10: case 11: dist = &kDist32x16; n_ecc = 4; break;
+        default: return false;
+      }
+      w = band_weights(X, Y, *dist, ecc, c, n_ecc);
+      for (int y = 0; y < Y; ++y)
+        for (int x = 0; x < X; ++x) at(num, x, y) = scale_i(X, x) * scale_i(Y, y) / (double(X) * Y);
+      break;
+    }
+  }
+  for (int i = 0; i < X * Y; ++i) {
+    const double v = num[i] / w[i];
+    if (i > 0 && !(v > 0.0 && std::isfinite(v))) return false;
+    out[i] = v;
+  }
+  return true;
+}
+
+void inverse_transform_matrix_f64(int n, double* out) {
+  for (int r = 0; r < n; ++r)
+    for (int k = 0; k < n; ++k) out[r * n + k] = ortho(n, r, k) / scale_i(n, k);
+}
+
+// J.2.4: Weight(sad, mul) as binary32 bits; mul <= 0.
+static float epf_weight(int32_t sad, int32_t mul) {
+  const int64_t pre = int64_t(sad < 507 ? sad : 507) << 6;
+  const int64_t prod = pre * mul;
+  // floor division by 2^16 (prod <= 0)
+  const int64_t hi = (prod >= 0 ? prod / 65536 : -((-prod + 65535) / 65536)) + (127 << 7);
+  const uint32_t bits = uint32_t(hi) << 16;
+  float f;
+  std::memcpy(&f, &bits, 4);
+  return f;
+}
+
+void epf_mul_table(int sigma_shift, int32_t* table) {
+  std::memset(table, 0, sizeof(int32_t) * 673);
+  int32_t mul = -32768;
+  for (int sigma = 16; sigma <= 672; sigma += 4) {
+    while (mul < 0 && !(epf_weight(sigma >> sigma_shift, mul) > 0.5f)) ++mul;
+    table[sigma] = mul;
+  }
+  // Between the computed points the step is truncated toward zero.
+  for (int sigma = 16; sigma < 672; sigma += 4) {
+    const int32_t step = (table[sigma + 4] - table[sigma]) / 4;
+    for (int i = 1; i < 4; ++i) table[sigma + i] = table[sigma] + i * step;
+  }
+}
+
+bool build_tables(DeviceTables* t) {
+  std::memset(t, 0, sizeof(*t));
+  std::vector<double> m(32 * 32);
+  inverse_transform_matrix_f64(8, m.data());
+  for (int i = 0; i < 64; ++i) t->t8[i] = float(m[i]);
+  inverse_transform_matrix_f64(16, m.data());
+  for (int i = 0; i < 256; ++i) t->t16[i] = float(m[i]);
+  inverse_transform_matrix_f64(32, m.data());
+  for (int i = 0; i < 1024; ++i) t->t32[i] = float(m[i]);
+  inverse_transform_matrix_f64(4, m.data());
+  for (int half = 0; half < 2; ++half)
+    for (int j = 0; j < 4; ++j)
+      for (int i = 0; i < 4; ++i) t->m4[(4 * half + j) * 8 + half + 2 * i] = float(m[j * 4 + i]);
+  // LLF from DC along one axis of a side with n DC samples (n = 2, 4):
+  // a[x][i] = F_n[x][i] * ScaleF(n, 8 n, x) / n with the forward transform
+  // F_n = n diag(I(n, .)) Q_n^T.
+  for (int n : {2, 4}) {
+    float* a = n == 2 ? t->a16 : t->a32;
+    for (int x = 0; x < n; ++x)
+      for (int i = 0; i < n; ++i)
+        a[x * n + i] = float(scale_i(n, x) * ortho(n, i, x) * scale_f(n, 8 * n, x));
+  }
+  std::vector<double> dq(1024);
+  for (int s = 0; s < kNumStrategies; ++s) {
+    const int sz = 64 * blocks_x(s) * blocks_y(s);
+    for (int c = 0; c < 3; ++c) {
+      if (!dequant_matrix_f64(s, c, dq.data())) return false;
+      for (int i = 0; i < sz; ++i) t->dq[dq_offset(s) + c * sz + i] = float(dq[i]);
+    }
+  }
+  for (int shift = 0; shift <= 8; ++shift) epf_mul_table(shift, t->mul_table[shift]);
+  return true;
+}
+
+}  // namespace jxlr

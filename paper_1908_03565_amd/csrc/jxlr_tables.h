@@ -1,0 +1,60 @@
+// Host-built constant tables of the VarDCT reconstruction library, and the
+// device-side layout they are uploaded in.
+#pragma once
+
+#include <cstdint>
+
+namespace jxlr {
+
+// Number of transform types the library reconstructs (C.5.4 values 0..11).
+constexpr int kNumStrategies = 12;
+
+// Varblock size in 8x8 blocks of transform type s (I.2.5: "DCT N x M" is
+// max(8, N) wide and max(8, M) tall).
+inline int blocks_x(int s) {
+  static const int8_t w[15] = {1, 1, 1, 1, 2, 4, 2, 1, 4, 1, 4, 2, 1, 1, 1};
+  return w[s];
+}
+inline int blocks_y(int s) {
+  static const int8_t h[15] = {1, 1, 1, 1, 2, 4, 1, 2, 1, 4, 2, 4, 1, 1, 1};
+  return h[s];
+}
+
+// Offsets (in floats) of the per-type dequantization matrices inside
+// DeviceTables::dq; channel c of type s starts at dq_offset(s) + c * bx * by.
+int dq_offset(int s);
+constexpr int kDqFloats = 3 * (4 * 64 + 256 + 1024 + 2 * 128 + 2 * 256 + 2 * 512);
+
+// Everything the kernels read that does not depend on the frame.  One
+// instance lives in device memory per context.
+struct DeviceTables {
+  // Inverse 1-D transform matrices, row n = output sample, column k = input
+  // coefficient (I.2.1 and the generated transforms).
+  float t8[8 * 8];
+  float t16[16 * 16];
+  float t32[32 * 32];
+  // DCT4x4 separable pass on an 8-vector (I.2.4.3): two interleaved 4-point
+  // inverse transforms; m4[4 s + j][s + 2 i] = T4[j][i].
+  float m4[8 * 8];
+  // LLF from DC (I.2.7.2), one axis: a16[x][i] for 2 DC samples of a
+  // 16-pixel side, a32[x][i] for 4 samples of a 32-pixel side, with the
+  // ScaleF factor and the 1 / (samples) division folded in.
+  float a16[2 * 2];
+  float a32[4 * 4];
+  // Dequantization matrices (C.6.1, defaults of C.6.1.1), row-major [y][x].
+  float dq[kDqFloats];
+  // mul_table of J.2.4 for sigma 0..672 (entries below 16 unused), one per
+  // kSigmaShift value 0..8.
+  int32_t mul_table[9][673];
+};
+
+// Fills t on the host.  Returns false if a dequantization matrix entry is not
+// positive and finite (C.6.1).
+bool build_tables(DeviceTables* t);
+
+// The same tables in double precision, for the host-side cross-checks.
+bool dequant_matrix_f64(int s, int c, double* out);
+void inverse_transform_matrix_f64(int n, double* out);
+void epf_mul_table(int sigma_shift, int32_t* table);
+
+}  // namespace jxlr

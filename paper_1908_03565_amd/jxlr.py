@@ -1,0 +1,243 @@
+"""ctypes binding of libjxlr.so (C ABI in include/jxlr.h).
+
+Argument marshalling only: every step of the reconstruction runs in the HIP
+library.  PyTorch provides device memory (tensors) and streams.  Loading fails
+loudly when the library has not been built; nothing here falls back to a CPU
+implementation.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libjxlr.so")
+
+JXLR_OUT_F32, JXLR_OUT_U8_SRGB, JXLR_OUT_U16_SRGB = 0, 1, 2
+STATUS = ["ok", "null", "size", "strategy", "align", "quant", "dequant", "param",
+          "workspace", "hip", "device_validation"]
+
+
+class FrameParams(C.Structure):
+    _fields_ = [
+        ("xsize", C.c_uint32), ("ysize", C.c_uint32),
+        ("global_scale", C.c_uint32),
+        ("dc_mul", C.c_float * 3),
+        ("extra_levels", C.c_int32 * 3),
+        ("kx_dc", C.c_float), ("kb_dc", C.c_float),
+        ("gab", C.c_int32),
+        ("gab_w1", C.c_float * 3), ("gab_w2", C.c_float * 3),
+        ("epf_iters", C.c_int32),
+        ("epf_weight_min", C.c_float),
+        ("epf_scale", C.c_float * 3),
+        ("epf_sharp_lut", C.c_float * 8),
+        ("epf_range_max", C.c_float), ("epf_range_mul", C.c_float),
+        ("epf_quant_mul", C.c_float),
+        ("epf_sigma_max", C.c_int32),
+        ("epf_sigma_shift", C.c_int32),
+        ("opsin_inv", C.c_float * 9),
+        ("opsin_bias", C.c_float * 3),
+        ("target_nits_div50", C.c_int32),
+        ("out_format", C.c_int32),
+    ]
+
+
+class FrameIO(C.Structure):
+    _fields_ = [
+        ("ac", C.c_void_p * 3), ("ac_stride", C.c_size_t),
+        ("dc", C.c_void_p * 3), ("dc_stride", C.c_size_t),
+        ("strategy", C.c_void_p), ("qf_minus_1", C.c_void_p), ("sharpness", C.c_void_p),
+        ("map_stride", C.c_size_t),
+        ("cfl_kx", C.c_void_p), ("cfl_kb", C.c_void_p), ("cfl_stride", C.c_size_t),
+        ("out", C.c_void_p * 3), ("out_stride", C.c_size_t),
+    ]
+
+
+class JxlrError(RuntimeError):
+    def __init__(self, status, what=""):
+        self.status = status
+        name = STATUS[status] if 0 <= status < len(STATUS) else str(status)
+        super().__init__(f"jxlr {what}: status {status} ({name})")
+
+
+_LIB = None
+
+# Entry points declared in include/jxlr.h, with their ctypes signatures.
+_SIGS = {
+    "jxlr_status_string": ([C.c_int], C.c_char_p),
+    "jxlr_params_default": ([C.POINTER(FrameParams), C.c_uint32, C.c_uint32], C.c_int),
+    "jxlr_create": ([C.POINTER(C.c_void_p), C.c_int], C.c_int),
+    "jxlr_destroy": ([C.c_void_p], None),
+    "jxlr_validate_maps_host": ([C.POINTER(FrameParams), C.c_void_p, C.c_void_p, C.c_void_p,
+                                 C.c_size_t], C.c_int),
+    "jxlr_workspace_bytes": ([C.POINTER(FrameParams)], C.c_size_t),
+    "jxlr_decode": ([C.c_void_p, C.POINTER(FrameParams), C.POINTER(FrameIO), C.c_void_p,
+                     C.c_size_t, C.c_void_p], C.c_int),
+    "jxlr_reconstruct": ([C.c_void_p, C.POINTER(FrameParams), C.POINTER(FrameIO), C.c_void_p,
+                          C.c_size_t, C.c_void_p], C.c_int),
+    "jxlr_epf_pass": ([C.c_void_p, C.POINTER(FrameParams), C.POINTER(FrameIO), C.c_void_p,
+                       C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
+    "jxlr_finish": ([C.c_void_p, C.POINTER(FrameParams), C.POINTER(FrameIO), C.c_void_p,
+                     C.c_size_t, C.c_void_p], C.c_int),
+    "jxlr_get_device_status": ([C.c_void_p, C.c_void_p], C.c_int),
+}
+
+
+def lib():
+    """Loads libjxlr.so; raises if it has not been built."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(
+                f"{LIB_PATH} is missing: build it with paper_1908_03565_amd/build.py "
+                "(or __graft_entry__.build()); there is no fallback path")
+        L = C.CDLL(LIB_PATH)
+        for name, (args, res) in _SIGS.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _LIB = L
+    return _LIB
+
+
+def exported_symbols():
+    return list(_SIGS)
+
+
+def _check(st, what):
+    if st != 0:
+        raise JxlrError(st, what)
+
+
+def params(xsize, ysize, **overrides):
+    """Frame parameters: the library's defaults, then `overrides`."""
+    p = FrameParams()
+    _check(lib().jxlr_params_default(C.byref(p), int(xsize), int(ysize)), "params_default")
+    for k, v in overrides.items():
+        cur = getattr(p, k)
+        if isinstance(cur, C.Array):
+            vals = list(np.asarray(v).ravel())
+            if len(vals) != len(cur):
+                raise ValueError(k)
+            for i, x in enumerate(vals):
+                cur[i] = type(cur[0])(x) if isinstance(cur[0], int) else float(x)
+        else:
+            setattr(p, k, v)
+    return p
+
+
+def validate_maps_host(p, frame):
+    st = np.ascontiguousarray(frame["strategy"], np.uint8)
+    qf = np.ascontiguousarray(frame["qf"], np.uint8)
+    sh = np.ascontiguousarray(frame["sharpness"], np.uint8) if "sharpness" in frame else None
+    return lib().jxlr_validate_maps_host(C.byref(p), st.ctypes.data, qf.ctypes.data,
+                                         sh.ctypes.data if sh is not None else None,
+                                         st.shape[1])
+
+
+def workspace_bytes(p):
+    return lib().jxlr_workspace_bytes(C.byref(p))
+
+
+def _stream_handle(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+class DeviceFrame:
+    """A frame's input planes resident in device memory (torch tensors)."""
+
+    def __init__(self, frame, device="cuda"):
+        import torch
+        t = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a, dtype=dt)).to(device)
+        self.xsize, self.ysize = int(frame["xsize"]), int(frame["ysize"])
+        self.ac = t(frame["ac"], np.int32)
+        self.dc = t(frame["dc"], np.int32)
+        self.strategy = t(frame["strategy"], np.uint8)
+        self.qf = t(frame["qf"], np.uint8)
+        self.sharpness = t(frame["sharpness"], np.uint8)
+        self.cfl_kx = t(frame["cfl_kx"], np.float32)
+        self.cfl_kb = t(frame["cfl_kb"], np.float32)
+
+    def io(self, out=None):
+        io = FrameIO()
+        for c in range(3):
+            io.ac[c] = self.ac[c].data_ptr()
+            io.dc[c] = self.dc[c].data_ptr()
+        io.ac_stride = self.ac.shape[2]
+        io.dc_stride = self.dc.shape[2]
+        io.strategy = self.strategy.data_ptr()
+        io.qf_minus_1 = self.qf.data_ptr()
+        io.sharpness = self.sharpness.data_ptr()
+        io.map_stride = self.strategy.shape[1]
+        io.cfl_kx = self.cfl_kx.data_ptr()
+        io.cfl_kb = self.cfl_kb.data_ptr()
+        io.cfl_stride = self.cfl_kx.shape[1]
+        if out is not None:
+            for c in range(3):
+                io.out[c] = out[c].data_ptr()
+            io.out_stride = out.shape[2]
+        return io
+
+
+_OUT_DTYPE = {JXLR_OUT_F32: "float32", JXLR_OUT_U8_SRGB: "uint8", JXLR_OUT_U16_SRGB: "uint16"}
+
+
+class Context:
+    """A jxlr context on one HIP device."""
+
+    def __init__(self, device=0):
+        self.device = device
+        h = C.c_void_p()
+        _check(lib().jxlr_create(C.byref(h), int(device)), "create")
+        self.handle = h
+
+    def close(self):
+        if self.handle:
+            lib().jxlr_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # --- allocation helpers (torch device memory) ---
+    def empty_xyb(self, p):
+        import torch
+        return torch.empty((3, p.ysize, p.xsize), dtype=torch.float32, device=f"cuda:{self.device}")
+
+    def empty_out(self, p):
+        import torch
+        dt = getattr(torch, _OUT_DTYPE[p.out_format])
+        return torch.empty((3, p.ysize, p.xsize), dtype=dt, device=f"cuda:{self.device}")
+
+    def workspace(self, p):
+        import torch
+        return torch.empty(workspace_bytes(p), dtype=torch.uint8, device=f"cuda:{self.device}")
+
+    # --- entry points ---
+    def reconstruct(self, p, df, xyb, stream=None):
+        _check(lib().jxlr_reconstruct(self.handle, C.byref(p), C.byref(df.io()), xyb.data_ptr(),
+                                      xyb.shape[2], _stream_handle(stream)), "reconstruct")
+
+    def epf_pass(self, p, df, xyb_in, xyb_out, guide=None, sigma=None, stream=None):
+        _check(lib().jxlr_epf_pass(self.handle, C.byref(p), C.byref(df.io()), xyb_in.data_ptr(),
+                                   xyb_out.data_ptr(), xyb_in.shape[2],
+                                   guide.data_ptr() if guide is not None else None,
+                                   sigma.data_ptr() if sigma is not None else None,
+                                   _stream_handle(stream)), "epf_pass")
+
+    def finish(self, p, df, xyb, out, stream=None):
+        _check(lib().jxlr_finish(self.handle, C.byref(p), C.byref(df.io(out)), xyb.data_ptr(),
+                                 xyb.shape[2], _stream_handle(stream)), "finish")
+
+    def decode(self, p, df, out, ws, stream=None, io=None):
+        io = df.io(out) if io is None else io
+        _check(lib().jxlr_decode(self.handle, C.byref(p), C.byref(io), ws.data_ptr(),
+                                 ws.numel(), _stream_handle(stream)), "decode")
+
+    def device_status(self, stream=None):
+        return lib().jxlr_get_device_status(self.handle, _stream_handle(stream))

@@ -1,0 +1,24 @@
+// Test-only shim: exposes the library's host-built constant tables to the
+// CPU tests, which compare them with the oracle's independently built ones.
+#include <cstddef>
+#include <cstdint>
+
+#include "jxlr_tables.h"
+
+static jxlr::DeviceTables g_tables;
+
+extern "C" {
+int shim_dequant(int s, int c, double* out) { return jxlr::dequant_matrix_f64(s, c, out) ? 1 : 0; }
+void shim_inverse(int n, double* out) { jxlr::inverse_transform_matrix_f64(n, out); }
+void shim_mul_table(int shift, int32_t* t) { jxlr::epf_mul_table(shift, t); }
+int shim_build() { return jxlr::build_tables(&g_tables) ? 1 : 0; }
+const float* shim_t8() { return g_tables.t8; }
+const float* shim_t16() { return g_tables.t16; }
+const float* shim_t32() { return g_tables.t32; }
+const float* shim_m4() { return g_tables.m4; }
+const float* shim_a16() { return g_tables.a16; }
+const float* shim_a32() { return g_tables.a32; }
+const float* shim_dq() { return g_tables.dq; }
+const int32_t* shim_mul(int shift) { return g_tables.mul_table[shift]; }
+int shim_dq_offset(int s) { return jxlr::dq_offset(s); }
+}

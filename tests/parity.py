@@ -1,0 +1,97 @@
+"""Parity helpers shared by the GPU tests, smoke() and bench.py.
+
+Runs a frame through the GPU path stage by stage (via the C-ABI binding) and
+through the FP64 oracle, and compares them.  The edge-preserving filter turns
+real values into integers twice (the 8-bit guide samples and the truncated
+sigma, J.2.2 and J.2.4); binary32 and binary64 inputs that differ in the last
+bits can land on different sides of such a boundary.  Both sides' integer
+decisions are compared directly; pixels whose filter footprint contains a
+differing decision are counted and reported separately, and the tolerance is
+applied to all other pixels.
+"""
+import numpy as np
+
+# Max-abs tolerance on [0,1]-scaled linear RGB for the FP32 form.
+RGB_TOL = 1e-4
+
+
+def mirror_index(idx, size):
+    """6.5 mirroring of an index array."""
+    idx = np.asarray(idx).copy()
+    while np.any((idx < 0) | (idx >= size)):
+        idx = np.where(idx < 0, -idx - 1, idx)
+        idx = np.where(idx >= size, 2 * size - 1 - idx, idx)
+    return idx
+
+
+def dilate(mask, dxs, dys):
+    """out[y, x] = any mask[mirror(y + dy), mirror(x + dx)] over the offsets."""
+    H, W = mask.shape
+    out = np.zeros_like(mask)
+    if not mask.any():
+        return out
+    for dy in dys:
+        rows = mask[mirror_index(np.arange(H) + dy, H)]
+        for dx in dxs:
+            out |= rows[:, mirror_index(np.arange(W) + dx, W)]
+    return out
+
+
+# Footprint of one EPF output pixel: guide samples at x-4..x+6, y-4..y+4
+# (patches of x-1..x+2, y-1..y+1 around offsets -3..4, -3..3); input samples
+# inside that.
+EPF_DX = range(-4, 7)
+EPF_DY = range(-4, 5)
+
+
+def affected_mask(p, gpu_passes, orc_passes):
+    """Pixels whose value may legitimately differ because an integer decision
+    differs.  gpu_passes / orc_passes: lists of (guide (3,H,W) u8, sigma (Hb,Wb))."""
+    H, W = p.ysize, p.xsize
+    bad = np.zeros((H, W), bool)
+    stats = []
+    for (gg, sg), (go, so) in zip(gpu_passes, orc_passes):
+        gmis = np.any(gg != go, axis=0)
+        smis_b = sg != so
+        smis = np.kron(smis_b, np.ones((8, 8), bool))[:H, :W]
+        new = dilate(gmis | bad, EPF_DX, EPF_DY) | smis
+        stats.append(dict(guide_flips=int(gmis.sum()), sigma_flips=int(smis_b.sum())))
+        bad = new
+    return bad, stats
+
+
+def gpu_stages(ctx, p, df):
+    """Runs the stage entry points; returns numpy arrays of every stage."""
+    import torch
+    xyb = ctx.empty_xyb(p)
+    ctx.reconstruct(p, df, xyb)
+    res = {"recon": xyb.cpu().numpy(), "epf": []}
+    Hb, Wb = (p.ysize + 7) // 8, (p.xsize + 7) // 8
+    cur = xyb
+    for _ in range(p.epf_iters):
+        nxt = ctx.empty_xyb(p)
+        guide = torch.empty((3, p.ysize, p.xsize), dtype=torch.uint8, device=cur.device)
+        sigma = torch.empty((Hb, Wb), dtype=torch.int32, device=cur.device)
+        ctx.epf_pass(p, df, cur, nxt, guide, sigma)
+        res["epf"].append((nxt.cpu().numpy(), guide.cpu().numpy(), sigma.cpu().numpy()))
+        cur = nxt
+    out = ctx.empty_out(p)
+    ctx.finish(p, df, cur, out)
+    res["out"] = out.cpu().numpy()
+    torch.cuda.synchronize()
+    return res
+
+
+def compare_rgb(p, gpu, orc):
+    """Max-abs error of the final [0,1]-scaled RGB outside flip-affected
+    pixels, plus the flip statistics."""
+    mask, stats = affected_mask(p, [(g, s) for _, g, s in gpu["epf"]],
+                                [(g, s) for _, g, s in orc["epf"]])
+    if p.gab:
+        mask = dilate(mask, range(-1, 2), range(-1, 2))
+    err = np.abs(gpu["out"].astype(np.float64) - orc["rgb"])
+    ok = ~mask
+    return dict(max_err=float(err[:, ok].max()) if ok.any() else 0.0,
+                max_err_affected=float(err[:, mask].max()) if mask.any() else 0.0,
+                affected=int(mask.sum()), pixels=int(mask.size), passes=stats,
+                max_abs_ref=float(np.abs(orc["rgb"]).max()))

@@ -1,0 +1,162 @@
+"""CPU tests of the C-ABI library: exports, defaults, host validation, and the
+library's host-built tables against the oracle's (both written independently
+from the draft).  No GPU is touched."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1908_03565_amd import jxlr as J
+from paper_1908_03565_amd import workload as wl
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _header_functions():
+    txt = open(os.path.join(ROOT, "include", "jxlr.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(jxlr_[a-z_0-9]+)\s*\(", txt)))
+
+
+def test_library_exports_every_header_function():
+    names = _header_functions()
+    assert len(names) >= 11
+    lib = J.lib()
+    for n in names:
+        assert hasattr(lib, n), n
+        assert n in J.exported_symbols(), n
+
+
+def test_status_strings():
+    for s in range(11):
+        assert J.lib().jxlr_status_string(s)
+
+
+def test_defaults_agree_with_oracle():
+    p = J.params(64, 48)
+    q = O.params(64, 48)
+    for name, _ in J.FrameParams._fields_:
+        if name == "out_format":
+            continue
+        a, b = getattr(p, name), getattr(q, name)
+        if isinstance(a, C.Array):
+            np.testing.assert_allclose(list(a), list(b), rtol=1e-7, err_msg=name)
+        else:
+            assert a == pytest.approx(b, rel=1e-7), name
+
+
+def _frame(W=64, H=64, s=0):
+    Wb, Hb = (W + 7) // 8, (H + 7) // 8
+    return dict(strategy=np.full((Hb, Wb), s, np.uint8), qf=np.zeros((Hb, Wb), np.uint8),
+                sharpness=np.zeros((Hb, Wb), np.uint8))
+
+
+def test_validate_maps_host():
+    p = J.params(64, 64)
+    assert J.validate_maps_host(p, _frame()) == 0
+    f = _frame(); f["strategy"][0, 1] = 4
+    assert J.validate_maps_host(p, f) == 4  # misaligned
+    f = _frame(); f["strategy"][0, 1] = 7; f["strategy"][1, 0] = 6
+    assert J.validate_maps_host(p, f) == 4  # DCT16x8 at block (0,1) overlaps DCT8x16 at (1,0)
+    p24 = J.params(24, 24)
+    f = _frame(24, 24); f["strategy"][2, 2] = 4
+    assert J.validate_maps_host(p24, f) == 4  # out of bounds
+    for bad in (12, 13, 14, 15, 200):
+        f = _frame(); f["strategy"][3, 3] = bad
+        assert J.validate_maps_host(p, f) == 3
+    f = _frame(s=4); f["qf"][1, 1] = 5
+    assert J.validate_maps_host(p, f) == 5  # quant field not uniform in a varblock
+    f = _frame(); f["sharpness"][2, 2] = 8
+    assert J.validate_maps_host(p, f) == 7
+    for fr in (wl.small(), wl.small(83, 45, seed=3), wl.c1()):
+        assert J.validate_maps_host(J.params(fr["xsize"], fr["ysize"]), fr) == 0
+
+
+def test_parameter_ranges():
+    f = _frame()
+    for k, v in [("epf_weight_min", 1.5), ("epf_sigma_max", 700), ("epf_sigma_shift", 9),
+                 ("epf_iters", 4), ("global_scale", 0), ("target_nits_div50", 0),
+                 ("out_format", 3)]:
+        p = J.params(64, 64, **{k: v})
+        assert J.validate_maps_host(p, f) == 7, k
+        assert J.workspace_bytes(p) == 0
+    assert J.validate_maps_host(J.params(0, 8), _frame(8, 8)) == 2
+
+
+def test_workspace_bytes():
+    p = J.params(100, 50, epf_iters=0)
+    assert J.workspace_bytes(p) >= 3 * 100 * 50 * 4
+    p2 = J.params(100, 50, epf_iters=2)
+    assert J.workspace_bytes(p2) == 2 * J.workspace_bytes(p)
+
+
+# --- the library's constant tables versus the oracle's --------------------
+
+@pytest.fixture(scope="module")
+def shim(tmp_path_factory):
+    out = tmp_path_factory.mktemp("shim") / "libtableshim.so"
+    csrc = os.path.join(ROOT, "paper_1908_03565_amd", "csrc")
+    subprocess.run(["g++", "-std=c++17", "-O2", "-shared", "-fPIC", "-I", csrc,
+                    os.path.join(ROOT, "tests", "native", "table_shim.cpp"),
+                    os.path.join(csrc, "jxlr_tables.cpp"), "-o", str(out)], check=True)
+    L = C.CDLL(str(out))
+    for f in ("shim_t8", "shim_t16", "shim_t32", "shim_m4", "shim_a16", "shim_a32", "shim_dq"):
+        getattr(L, f).restype = C.POINTER(C.c_float)
+    L.shim_mul.restype = C.POINTER(C.c_int32)
+    assert L.shim_build() == 1
+    return L
+
+
+def _arr(ptr, n):
+    return np.ctypeslib.as_array(ptr, shape=(n,)).copy()
+
+
+def test_dequant_tables_match_oracle(shim):
+    for s in range(12):
+        bx, by = O.varblock_size(s)
+        for c in range(3):
+            buf = np.zeros(bx * by)
+            assert shim.shim_dequant(s, c, buf.ctypes.data_as(C.POINTER(C.c_double))) == 1
+            ref = O.dequant_matrix(s, c).ravel()
+            np.testing.assert_allclose(buf[1:], ref[1:], rtol=1e-12, err_msg=f"{s},{c}")
+            f32 = _arr(shim.shim_dq(), 9984)[shim.shim_dq_offset(s) + c * bx * by:][:bx * by]
+            np.testing.assert_allclose(f32[1:], ref[1:], rtol=1e-7)
+
+
+def test_transform_tables_match_oracle(shim):
+    for n in (4, 8, 16, 32):
+        buf = np.zeros(n * n)
+        shim.shim_inverse(n, buf.ctypes.data_as(C.POINTER(C.c_double)))
+        np.testing.assert_allclose(buf.reshape(n, n), O.idct_matrix(n), atol=1e-13)
+    for n, f in ((8, shim.shim_t8), (16, shim.shim_t16), (32, shim.shim_t32)):
+        np.testing.assert_allclose(_arr(f(), n * n).reshape(n, n), O.idct_matrix(n), rtol=2e-7,
+                                   atol=2e-7)
+    t4 = O.idct_matrix(4)
+    m4 = _arr(shim.shim_m4(), 64).reshape(8, 8)
+    ref = np.zeros((8, 8))
+    for h in range(2):
+        for j in range(4):
+            for i in range(4):
+                ref[4 * h + j, h + 2 * i] = t4[j, i]
+    np.testing.assert_allclose(m4, ref, atol=2e-7)
+
+
+def test_llf_tables_match_oracle(shim):
+    # a16 / a32 are the one-axis LLF-from-DC factors: the oracle's I.2.7 on
+    # DCT16x8 (2 x 1 DC samples) and DCT32x8 (4 x 1) gives them column by column.
+    for s, n, f in ((6, 2, shim.shim_a16), (8, 4, shim.shim_a32)):
+        a = _arr(f(), n * n).reshape(n, n)
+        ref = np.stack([O.llf_from_dc(s, e.reshape(1, n)).ravel() for e in np.eye(n)], axis=1)
+        np.testing.assert_allclose(a, ref, atol=2e-7)
+
+
+def test_mul_tables_match_oracle(shim):
+    for shift in range(0, 9):
+        t = np.zeros(673, np.int32)
+        shim.shim_mul_table(shift, t.ctypes.data_as(C.POINTER(C.c_int32)))
+        np.testing.assert_array_equal(t, O.mul_table(shift))
+        np.testing.assert_array_equal(_arr(shim.shim_mul(shift), 673), O.mul_table(shift))
