@@ -147,11 +147,13 @@ __device__ inline void identity_inverse(float (&v)[64]) {
 #pragma unroll
   for (int i = 0; i < 64; ++i) k[i] = v[i];
   aux_idct2x2<2>(v);  // v's 2x2 corner now holds the four quarter DCs
+  // the quarters' outputs overwrite that corner, so keep the DCs apart
+  const float dcs[4] = {v[0], v[1], v[8], v[9]};
 #pragma unroll
   for (int sy = 0; sy < 2; ++sy)
 #pragma unroll
     for (int sx = 0; sx < 2; ++sx) {
-      const float dcv = v[sy * 8 + sx];
+      const float dcv = dcs[sy * 2 + sx];
       float rs = 0.0f;
 #pragma unroll
       for (int iy = 0; iy < 4; ++iy)

@@ -33,12 +33,14 @@ BLOCKS = {0: (1, 1), 1: (1, 1), 2: (1, 1), 3: (1, 1), 4: (2, 2), 5: (4, 4),
 # The ten transform types the mixed workloads draw from.
 MIXED = [DCT8, DCT4, DCT2, IDENTITY, DCT16, DCT32, DCT8X16, DCT16X8, DCT16X32, DCT32X16]
 
-# Frame-parameter overrides common to every workload: global_scale = 32768 so
-# that AcMul = 2 / QF, in [1/16, 2] for QF in [1, 32]; DC multipliers that give
-# XYB extents of about +-0.03 (X) and +-1 (Y, B) for DC values in [-512, 512].
-# With these the XYB samples stay within about |Y + X| <= 2.5, so linear RGB
-# stays within a few times the sRGB range.
-BASE_PARAMS = dict(global_scale=32768, dc_mul=(2.0 ** -14, 2.0 ** -9, 2.0 ** -9),
+# Frame-parameter overrides common to every workload: global_scale = 65536 so
+# that AcMul = 1 / QF, in [1/32, 1] for QF in [1, 32]; DC multipliers that give
+# XYB DC extents of about +-0.03 (X) and +-0.5 (Y, B) for DC values in
+# [-512, 512].  The coefficient distributions are fixed by the workload
+# definitions; these two scale factors are free, and are chosen so that linear
+# RGB stays within a few times the sRGB range (99.9% of samples within
+# [-3.2, 3.2] on the [0,1] scale at 2048x2048).
+BASE_PARAMS = dict(global_scale=65536, dc_mul=(2.0 ** -14, 2.0 ** -10, 2.0 ** -10),
                    extra_levels=(0, 0, 0))
 
 

@@ -16,9 +16,17 @@ from tests import parity as P
 
 pytestmark = pytest.mark.gpu
 
-# XYB reconstruction: binary32 sums of up to 32 products per pass on values
-# of magnitude <= ~8; 4e-6 absolute is ~30 ulp at 8.
+# XYB reconstruction: binary32 sums of up to 32 products per pass; 4e-6 is
+# about 30 ulp at the magnitude 8 the mixed workloads reach.  Frames whose
+# samples grow larger (the default DCT32x8 B-channel bands give dequantization
+# entries up to ~450) are held to the same relative bound.
 XYB_TOL = 4e-6
+
+
+def xyb_err_ok(gpu, ref):
+    scale = np.maximum(1.0, np.abs(ref).max(axis=(1, 2)) / 8.0)
+    err = np.abs(gpu - ref).max(axis=(1, 2))
+    return bool(np.all(err <= XYB_TOL * scale)), err
 
 
 @pytest.fixture(scope="module")
@@ -48,9 +56,9 @@ def _single_strategy_frame(s, W, H, seed):
 def test_reconstruction_per_transform_type(ctx, s):
     f = _single_strategy_frame(s, 96, 64, seed=40 + s)
     p, q, gpu, orc = _run(ctx, f)
-    err = np.abs(gpu["recon"] - orc["recon"]).max()
-    print(f"type {s}: recon max err {err:.3g}")
-    assert err <= XYB_TOL
+    ok, err = xyb_err_ok(gpu["recon"], orc["recon"])
+    print(f"type {s}: recon max err per channel {err}")
+    assert ok
 
 
 @pytest.mark.parametrize("W,H", [(1, 1), (7, 5), (9, 17), (33, 31), (65, 40), (100, 3),
@@ -58,8 +66,8 @@ def test_reconstruction_per_transform_type(ctx, s):
 def test_reconstruction_ragged_sizes(ctx, W, H):
     f = wl.frame(W, H, seed=W * 1000 + H, epf_iters=2)
     p, q, gpu, orc = _run(ctx, f)
-    err = np.abs(gpu["recon"] - orc["recon"]).max()
-    assert err <= XYB_TOL
+    ok, err = xyb_err_ok(gpu["recon"], orc["recon"])
+    assert ok, err
     cmp = P.compare_rgb(p, gpu, orc)
     print(f"{W}x{H}: {cmp}")
     assert cmp["max_err"] <= P.RGB_TOL
@@ -70,7 +78,7 @@ def test_c1_full_size(ctx):
     # 256x256, every varblock DCT8, EPF off: no integer decisions at all
     f = wl.c1()
     p, q, gpu, orc = _run(ctx, f)
-    assert np.abs(gpu["recon"] - orc["recon"]).max() <= XYB_TOL
+    assert xyb_err_ok(gpu["recon"], orc["recon"])[0]
     err = np.abs(gpu["out"].astype(np.float64) - orc["rgb"]).max()
     print(f"c1 rgb max err {err:.3g}")
     assert err <= P.RGB_TOL
@@ -132,10 +140,17 @@ def test_srgb_output_codes(ctx, fmt, bits):
 
 
 def test_dc_only_frame_is_constant_per_varblock(ctx):
-    import torch
+    """A varblock whose DC samples are all equal and whose AC is zero decodes
+    to that constant (I.2.7 inverting I.2.6), for every transform type."""
     from paper_1908_03565_amd import jxlr as J
     f = wl.frame(160, 96, seed=5, epf_iters=0)
     f["ac"][:] = 0
+    bx = np.vectorize(lambda s: wl.BLOCKS[int(s)][0])(f["strategy"])
+    by = np.vectorize(lambda s: wl.BLOCKS[int(s)][1])(f["strategy"])
+    Hb, Wb = f["strategy"].shape
+    ty = (np.arange(Hb)[:, None] // by) * by
+    tx = (np.arange(Wb)[None, :] // bx) * bx
+    f["dc"] = np.ascontiguousarray(f["dc"][:, ty, tx])  # top-left DC everywhere
     p = J.params(160, 96, **f["params"])
     df = J.DeviceFrame(f)
     xyb = ctx.empty_xyb(p)
@@ -143,12 +158,9 @@ def test_dc_only_frame_is_constant_per_varblock(ctx):
     x = xyb.cpu().numpy()
     q = O.params(160, 96, **f["params"])
     np.testing.assert_allclose(x, O.reconstruct(q, f), atol=XYB_TOL)
-    # each varblock constant: compare with its top-left pixel
-    bx = np.vectorize(lambda s: wl.BLOCKS[int(s)][0])(f["strategy"])
-    by = np.vectorize(lambda s: wl.BLOCKS[int(s)][1])(f["strategy"])
-    for j in range(f["strategy"].shape[0]):
-        for i in range(f["strategy"].shape[1]):
-            tlx, tly = (i // bx[j, i]) * bx[j, i] * 8, (j // by[j, i]) * by[j, i] * 8
+    for j in range(Hb):
+        for i in range(Wb):
+            tlx, tly = tx[j, i] * 8, ty[j, i] * 8
             blk = x[:, 8 * j:8 * j + 8, 8 * i:8 * i + 8]
             assert np.abs(blk - x[:, tly:tly + 1, tlx:tlx + 1]).max() < 1e-5
 
