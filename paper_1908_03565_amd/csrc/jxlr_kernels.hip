@@ -336,6 +336,19 @@ __global__ __launch_bounds__(kThreads) void recon_kernel(ReconArgs a) {
 
 // ---------------------------------------------------------------------------
 // Edge-preserving filter (J.2), one pass.
+//
+// One workgroup per 64x32 output tile (two 32x32 regions side by side); each
+// thread filters an 8-pixel vertical strip of one column.  The tile and its
+// filter halo are staged in LDS once:
+//   s_in  input samples of columns x0-3..x0+68 and rows y0-3..y0+34 (the
+//         7x8 window of every output pixel);
+//   s_p   per channel, 32-bit words packing the guide bytes of 4 consecutive
+//         columns, for start columns x0-4..x0+66 and rows y0-4..y0+35.
+// A J.2.3 patch is 4 columns by 3 rows, so one v_sad_u8 on two such words is
+// one channel's distance over one patch row.  For a window offset (cx, cy)
+// the distance of the strip's pixel in row y is rs(y-1) + rs(y) + rs(y+1),
+// rs(y') = sum_c sad(P_c(x-1, y'), P_c(x-1+cx, y'+cy)); the strip's ten row
+// sums serve its eight overlapping patches.
 
 struct EpfArgs {
   int W, H, Wb, Hb;
@@ -347,7 +360,7 @@ struct EpfArgs {
   float* out;
   size_t stride;
   float minv[3], scale[3];
-  float weight_min;
+  uint32_t thr;  // weights below epf_weight_min: bit patterns below thr (a multiple of 2^16)
   float sharp_lut[8];
   float range_max, range_mul, quant_mul;
   float sigma_max;
@@ -358,9 +371,10 @@ struct EpfArgs {
   int* status;
 };
 
-constexpr int kEpfT = 32;                // output tile
-constexpr int kEpfW = kEpfT + 4 + 6;     // guide/input columns x0-4 .. x0+37
-constexpr int kEpfH = kEpfT + 4 + 4;     // rows y0-4 .. y0+35
+constexpr int kEpfTW = 64, kEpfTH = 32;  // output tile
+constexpr int kInW = 72, kInH = 38;      // s_in: columns x0-3.., rows y0-3..
+constexpr int kPW = 72, kPH = 40;        // s_p: start columns x0-4.., rows y0-4..
+constexpr int kGW = 19;                  // packed guide words per row: columns x0-4..x0+71
 
 __device__ inline uint32_t guide_byte(float v, float minv, float scale) {
   // J.2.2 in binary32: floor(clamp((v - min) * scale, 0, 255))
@@ -369,130 +383,188 @@ __device__ inline uint32_t guide_byte(float v, float minv, float scale) {
   return uint32_t(floorf(g));
 }
 
-__device__ inline float epf_weight(uint32_t sad, int mul) {
-  // J.2.4: ((min(sad, 507) << 6) * mul >> 16) + (127 << 7), as the top half
-  // of a binary32 bit pattern
-  const int pre = int(min(sad, 507u)) << 6;
-  const int high16 = ((pre * mul) >> 16) + (127 << 7);
-  return __uint_as_float(uint32_t(high16) << 16);
-}
-
-__global__ __launch_bounds__(kThreads) void epf_kernel(EpfArgs a) {
-  __shared__ float s_in[3][kEpfH][kEpfW];
-  __shared__ uint32_t s_g[kEpfH][kEpfW];
-  __shared__ float s_rng[3][16];
-  __shared__ int s_sigma[16];
-  __shared__ uint8_t s_raw[16], s_owner[16], s_strat[16];
-  __shared__ int s_ok;
+__global__ __launch_bounds__(kThreads, 2) void epf_kernel(EpfArgs a) {
+  __shared__ float s_in[3][kInH][kInW];
+  __shared__ uint32_t s_p[3][kPH][kPW];
+  __shared__ uint32_t s_w[3][kPH][kGW + 1];
+  __shared__ float s_rng[32];
+  __shared__ int s_mul[32];
+  __shared__ uint8_t s_raw[2][16], s_owner[2][16], s_strat[2][16];
+  __shared__ int s_ok[2];
 
   const int tid = threadIdx.x;
-  const int x0 = kEpfT * blockIdx.x, y0 = kEpfT * blockIdx.y;
+  const int x0 = kEpfTW * blockIdx.x, y0 = kEpfTH * blockIdx.y;
   const int gbx0 = x0 / 8, gby0 = y0 / 8;
-  const int nbx = min(4, a.Wb - gbx0), nby = min(4, a.Hb - gby0);
   const size_t plane = size_t(a.H) * a.stride;
 
-  for (int i = tid; i < kEpfH * kEpfW; i += kThreads) {
-    const int ly = i / kEpfW, lx = i % kEpfW;
-    const int gx = mirror(x0 - 4 + lx, a.W), gy = mirror(y0 - 4 + ly, a.H);
-    uint32_t g = 0;
-    for (int c = 0; c < 3; ++c) {
-      const float v = a.in[c * plane + size_t(gy) * a.stride + gx];
-      s_in[c][ly][lx] = v;
-      g |= guide_byte(v, a.minv[c], a.scale[c]) << (8 * c);
+  // A: input samples and packed guide words (4 columns per word).
+  for (int it = tid; it < kPH * kGW; it += kThreads) {
+    const int v = it / kGW, g = it % kGW;
+    const int gy = mirror(y0 - 4 + v, a.H);
+    uint32_t w0 = 0, w1 = 0, w2 = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int lxx = x0 - 4 + 4 * g + j;
+      const int gx = mirror(lxx, a.W);
+      const float* p = a.in + size_t(gy) * a.stride + gx;
+      const float v0 = p[0], v1 = p[plane], v2 = p[2 * plane];
+      w0 |= guide_byte(v0, a.minv[0], a.scale[0]) << (8 * j);
+      w1 |= guide_byte(v1, a.minv[1], a.scale[1]) << (8 * j);
+      w2 |= guide_byte(v2, a.minv[2], a.scale[2]) << (8 * j);
+      const int ci = 4 * g + j - 1, ri = v - 1;
+      if (ci >= 0 && ci < kInW && ri >= 0 && ri < kInH) {
+        s_in[0][ri][ci] = v0;
+        s_in[1][ri][ci] = v1;
+        s_in[2][ri][ci] = v2;
+      }
     }
-    s_g[ly][lx] = g;
+    s_w[0][v][g] = w0;
+    s_w[1][v][g] = w1;
+    s_w[2][v][g] = w2;
   }
-  if (tid < 16) {
-    const int bx = tid & 3, by = tid >> 2;
-    s_raw[tid] = (bx < nbx && by < nby) ? a.strategy[size_t(gby0 + by) * a.map_stride + gbx0 + bx]
-                                        : kAbsent;
+  if (tid < 32) {
+    const int r = tid >> 4, lb = tid & 15;
+    const int bx = gbx0 + 4 * r + (lb & 3), by = gby0 + (lb >> 2);
+    s_raw[r][lb] = (bx < a.Wb && by < a.Hb) ? a.strategy[size_t(by) * a.map_stride + bx] : kAbsent;
   }
   __syncthreads();
-  if (tid == 0) s_ok = scan_region(s_raw, nbx, nby, s_owner, s_strat);
-  // Per-block, per-channel range of `scaled` over the block's pixels inside
-  // the frame (J.2.4).
-  if (tid < 48) {
-    const int lb = tid & 15, c = tid >> 4;
-    const int bx = lb & 3, by = lb >> 2;
-    float lo = INFINITY, hi = -INFINITY;
-    if (bx < nbx && by < nby)
-      for (int yy = 0; yy < 8; ++yy)
-        for (int xx = 0; xx < 8; ++xx) {
-          const int gx = x0 + 8 * bx + xx, gy = y0 + 8 * by + yy;
-          if (gx >= a.W || gy >= a.H) continue;
-          const float sc = (s_in[c][4 + 8 * by + yy][4 + 8 * bx + xx] - a.minv[c]) * a.scale[c];
-          lo = fminf(lo, sc);
-          hi = fmaxf(hi, sc);
+
+  // B: guide words at every start column; C: region scans.
+  for (int it = tid; it < 3 * kPH * (kPW - 1); it += kThreads) {
+    const int c = it / (kPH * (kPW - 1));
+    const int rem = it % (kPH * (kPW - 1));
+    const int v = rem / (kPW - 1), u = rem % (kPW - 1);
+    s_p[c][v][u] = __builtin_amdgcn_alignbyte(s_w[c][v][(u >> 2) + 1], s_w[c][v][u >> 2], u & 3);
+  }
+  if ((tid & 63) == 0 && tid < 128) {
+    const int r = tid >> 6;
+    // a region right of the frame has no blocks: the scan marks all absent
+    const int nbx = max(0, min(4, a.Wb - (gbx0 + 4 * r))), nby = min(4, a.Hb - gby0);
+    s_ok[r] = scan_region(s_raw[r], nbx, nby, s_owner[r], s_strat[r]);
+  }
+  // Per-block range of `scaled` (J.2.4) over the block's pixels inside the
+  // frame: eight lanes per block, one row each, reduced across the lanes.
+  {
+    const int b = tid >> 3, r = tid & 7;
+    const int bxl = b & 7, byl = b >> 3;
+    const int gy = y0 + 8 * byl + r;
+    float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    if (gy < a.H)
+      for (int j = 0; j < 8; ++j) {
+        if (x0 + 8 * bxl + j >= a.W) break;
+        for (int c = 0; c < 3; ++c) {
+          const float sc = (s_in[c][3 + 8 * byl + r][3 + 8 * bxl + j] - a.minv[c]) * a.scale[c];
+          lo[c] = fminf(lo[c], sc);
+          hi[c] = fmaxf(hi[c], sc);
         }
-    s_rng[c][lb] = hi - lo;
+      }
+    float rg = 0.0f;
+    for (int c = 0; c < 3; ++c) {
+      for (int m = 1; m < 8; m <<= 1) {
+        lo[c] = fminf(lo[c], __shfl_xor(lo[c], m, 8));
+        hi[c] = fmaxf(hi[c], __shfl_xor(hi[c], m, 8));
+      }
+      if (hi[c] >= lo[c]) rg = fmaxf(rg, hi[c] - lo[c]);
+    }
+    if (r == 0) s_rng[b] = rg;
   }
   __syncthreads();
-  if (!s_ok && tid == 0) atomicOr(a.status, 1);
-  if (tid < 16) {
+
+  // D: sigma and mul per block; mul * 64 is stored, 1 marks "not filtered".
+  if (tid < 32) {
+    const int bxl = tid & 7, byl = tid >> 3;
+    const int r = bxl >> 2, lb = byl * 4 + (bxl & 3);
+    const int bx = gbx0 + bxl, by = gby0 + byl;
     int sig = 0;
-    const int bx = tid & 3, by = tid >> 2;
-    if (s_ok && s_strat[tid] != kAbsent) {
-      // range = largest all_r over the varblock
-      float r = 0.0f;
+    if (!s_ok[r] && lb == 0) atomicOr(a.status, 1);
+    if (s_ok[r] && s_strat[r][lb] != kAbsent) {
+      float rg = 0.0f;
       for (int m = 0; m < 16; ++m)
-        if (s_owner[m] == s_owner[tid])
-          r = fmaxf(r, fmaxf(s_rng[0][m], fmaxf(s_rng[1][m], s_rng[2][m])));
-      const size_t mi = size_t(gby0 + by) * a.map_stride + gbx0 + bx;
-      float sg = fminf(r, a.range_max) * a.range_mul * a.sharp_lut[a.sharp[mi] & 7];
+        if (s_owner[r][m] == s_owner[r][lb]) rg = fmaxf(rg, s_rng[(m >> 2) * 8 + 4 * r + (m & 3)]);
+      const size_t mi = size_t(by) * a.map_stride + bx;
+      float sg = fminf(rg, a.range_max) * a.range_mul * a.sharp_lut[a.sharp[mi] & 7];
       sg = fminf(sg, a.gscale_q * float(1 + a.qf[mi]) * a.quant_mul);
       sg = fminf(sg, a.sigma_max);
       sig = int(sg);  // truncation; sg >= 0
     }
-    s_sigma[tid] = sig;
-    if (a.sigma_dbg && bx < nbx && by < nby) a.sigma_dbg[size_t(gby0 + by) * a.Wb + gbx0 + bx] = sig;
+    s_mul[tid] = sig >= 16 ? a.mul_table[sig] * 64 : 1;
+    if (a.sigma_dbg && bx < a.Wb && by < a.Hb) a.sigma_dbg[size_t(by) * a.Wb + bx] = sig;
   }
   __syncthreads();
 
-  for (int j = 0; j < 4; ++j) {
-    const int lx = tid & 31, ly = (tid >> 5) + 8 * j;
-    const int gx = x0 + lx, gy = y0 + ly;
-    if (gx >= a.W || gy >= a.H) continue;
-    const int cxl = lx + 4, cyl = ly + 4;
-    const int sigma = s_sigma[(ly >> 3) * 4 + (lx >> 3)];
-    float out[3];
-    if (sigma < 16) {
-      for (int c = 0; c < 3; ++c) out[c] = s_in[c][cyl][cxl];
-    } else {
-      const int mul = a.mul_table[sigma];
-      uint32_t ref[3][4];
-#pragma unroll
-      for (int iy = 0; iy < 3; ++iy)
-#pragma unroll
-        for (int ix = 0; ix < 4; ++ix) ref[iy][ix] = s_g[cyl - 1 + iy][cxl - 1 + ix];
-      float sw = 0.0f, acc0 = 0.0f, acc1 = 0.0f, acc2 = 0.0f;
-      for (int cy = -3; cy <= 3; ++cy) {
-#pragma unroll
-        for (int cx = -3; cx <= 4; ++cx) {
-          uint32_t sad = 0;
-#pragma unroll
-          for (int iy = 0; iy < 3; ++iy)
-#pragma unroll
-            for (int ix = 0; ix < 4; ++ix)
-              sad = __builtin_amdgcn_sad_u8(ref[iy][ix], s_g[cyl + cy - 1 + iy][cxl + cx - 1 + ix], sad);
-          float w = epf_weight(sad, mul);
-          w = w < a.weight_min ? 0.0f : w;
-          sw += w;
-          acc0 = fmaf(w, s_in[0][cyl + cy][cxl + cx], acc0);
-          acc1 = fmaf(w, s_in[1][cyl + cy][cxl + cx], acc1);
-          acc2 = fmaf(w, s_in[2][cyl + cy][cxl + cx], acc2);
-        }
-      }
-      out[0] = acc0 / sw;
-      out[1] = acc1 / sw;
-      out[2] = acc2 / sw;
-    }
-    for (int c = 0; c < 3; ++c) a.out[c * plane + size_t(gy) * a.stride + gx] = out[c];
-    if (a.guide_dbg) {
-      const uint32_t g = s_g[cyl][cxl];
+  // E: the strip of 8 pixels of column x.
+  const int lx = tid & 63, strip = tid >> 6;
+  const int x = x0 + lx, ys = y0 + 8 * strip;
+  if (x >= a.W || ys >= a.H) return;
+  const int nrows = min(8, a.H - ys);
+  const int mul64 = s_mul[strip * 8 + (lx >> 3)];
+  float* o0 = a.out + size_t(ys) * a.stride + x;
+  if (a.guide_dbg) {
+    const int wg = (lx + 4) >> 2, sh = 8 * ((lx + 4) & 3);
+    for (int i = 0; i < nrows; ++i)
       for (int c = 0; c < 3; ++c)
-        a.guide_dbg[(size_t(c) * a.H + gy) * a.W + gx] = uint8_t(g >> (8 * c));
+        a.guide_dbg[(size_t(c) * a.H + ys + i) * a.W + x] =
+            uint8_t(s_w[c][8 * strip + 4 + i][wg] >> sh);
+  }
+  if (mul64 > 0) {  // sigma < 16: the pass leaves the pixel unchanged
+    for (int i = 0; i < nrows; ++i)
+      for (int c = 0; c < 3; ++c)
+        o0[c * plane + size_t(i) * a.stride] = s_in[c][8 * strip + 3 + i][lx + 3];
+    return;
+  }
+  // Weight(sad, mul) of J.2.4: ((min(sad,507) << 6) * mul >> 16) + (127 << 7),
+  // placed in the top half of a binary32 pattern, equals
+  // (min(sad,507) * 64 mul + (127 << 23)) with the low 16 bits cleared.
+  constexpr int kC = 127 << 23;
+  const uint32_t thr = a.thr;
+  uint32_t ref[10][3];
+#pragma unroll
+  for (int j = 0; j < 10; ++j)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) ref[j][c] = s_p[c][8 * strip + 3 + j][lx + 3];
+  float acc[8][4];
+#pragma unroll
+  for (int i = 0; i < 8; ++i)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[i][c] = 0.0f;
+
+  for (int cx = -3; cx <= 4; ++cx) {
+    uint32_t nb[16][3];
+    float inp[14][3];
+#pragma unroll
+    for (int j = 0; j < 16; ++j)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) nb[j][c] = s_p[c][8 * strip + j][lx + 3 + cx];
+#pragma unroll
+    for (int j = 0; j < 14; ++j)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) inp[j][c] = s_in[c][8 * strip + j][lx + 3 + cx];
+#pragma unroll
+    for (int cy = -3; cy <= 3; ++cy) {
+      uint32_t rs[10];
+#pragma unroll
+      for (int j = 0; j < 10; ++j) {
+        uint32_t s = __builtin_amdgcn_sad_u8(ref[j][0], nb[j + cy + 3][0], 0u);
+        s = __builtin_amdgcn_sad_u8(ref[j][1], nb[j + cy + 3][1], s);
+        rs[j] = __builtin_amdgcn_sad_u8(ref[j][2], nb[j + cy + 3][2], s);
+      }
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const uint32_t sad = min(rs[i] + rs[i + 1] + rs[i + 2], 507u);
+        const uint32_t t = uint32_t(__mul24(int(sad), mul64) + kC);
+        const float w = __uint_as_float(t >= thr ? (t & 0xFFFF0000u) : 0u);
+        acc[i][3] += w;
+        acc[i][0] = fmaf(w, inp[i + cy + 3][0], acc[i][0]);
+        acc[i][1] = fmaf(w, inp[i + cy + 3][1], acc[i][1]);
+        acc[i][2] = fmaf(w, inp[i + cy + 3][2], acc[i][2]);
+      }
     }
   }
+#pragma unroll
+  for (int i = 0; i < 8; ++i)
+    if (i < nrows)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) o0[c * plane + size_t(i) * a.stride] = acc[i][c] / acc[i][3];
 }
 
 // ---------------------------------------------------------------------------
@@ -796,7 +868,14 @@ jxlr_status jxlr_epf_pass(jxlr_ctx* ctx, const jxlr_frame_params* p, const jxlr_
   a.minv[0] = float(-0.03 * im3);
   a.minv[1] = a.minv[2] = 0.0f;
   for (int c = 0; c < 3; ++c) a.scale[c] = p->epf_scale[c];
-  a.weight_min = p->epf_weight_min;
+  {
+    // weights w < epf_weight_min are dropped; the weights are multiples of
+    // 2^16 in bit pattern, so compare against the next such multiple
+    float wm = p->epf_weight_min;
+    uint32_t bits;
+    std::memcpy(&bits, &wm, 4);
+    a.thr = wm <= 0.0f ? 0u : ((bits + 0xFFFFu) & 0xFFFF0000u);
+  }
   for (int i = 0; i < 8; ++i) a.sharp_lut[i] = p->epf_sharp_lut[i];
   a.range_max = p->epf_range_max;
   a.range_mul = p->epf_range_mul;
@@ -809,7 +888,7 @@ jxlr_status jxlr_epf_pass(jxlr_ctx* ctx, const jxlr_frame_params* p, const jxlr_
   a.status = ctx->status;
   DeviceGuard g(ctx->device);
   if (!g.ok) return JXLR_E_HIP;
-  dim3 grid((p->xsize + kEpfT - 1) / kEpfT, (p->ysize + kEpfT - 1) / kEpfT);
+  dim3 grid((p->xsize + kEpfTW - 1) / kEpfTW, (p->ysize + kEpfTH - 1) / kEpfTH);
   hipLaunchKernelGGL(epf_kernel, grid, dim3(kThreads), 0, stream, a);
   return launch_status(hipGetLastError());
 }
