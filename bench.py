@@ -76,18 +76,21 @@ def main():
     ctx = J.Context(0)
     df = J.DeviceFrame(frame)
     bufs = [ctx.empty_xyb(p), ctx.empty_xyb(p)]
+    info = ctx.empty_info(p)
     out = ctx.empty_out(p)
     stream = torch.cuda.current_stream()
     n_epf = p.epf_iters
 
     def step(evs):
-        # reconstruct -> EPF passes -> Gaborish + XYB -> RGB; an event after each
+        # block info + reconstruct -> EPF passes -> Gaborish + XYB -> RGB; an
+        # event after each
         evs[0].record(stream)
-        ctx.reconstruct(p, df, bufs[0], stream=stream)
+        ctx.block_info(p, df, info, stream=stream)
+        ctx.reconstruct(p, df, info, bufs[0], stream=stream)
         evs[1].record(stream)
         cur = 0
         for i in range(n_epf):
-            ctx.epf_pass(p, df, bufs[cur], bufs[1 - cur], stream=stream)
+            ctx.epf_pass(p, df, info, bufs[cur], bufs[1 - cur], stream=stream)
             cur = 1 - cur
             evs[2 + i].record(stream)
         ctx.finish(p, df, bufs[cur], out, stream=stream)

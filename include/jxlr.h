@@ -153,9 +153,9 @@ jxlr_status jxlr_validate_maps_host(const jxlr_frame_params* p, const uint8_t* s
                                     const uint8_t* qf_minus_1, const uint8_t* sharpness,
                                     size_t map_stride);
 
-/* Device workspace jxlr_decode needs for one frame: two XYB float planes sets
- * (3 * xsize * ysize * 4 bytes each; one when epf_iters == 0), 256-byte
- * aligned. */
+/* Device workspace jxlr_decode needs for one frame: the block-info map
+ * (Hb * Wb bytes) and two sets of XYB float planes (3 * xsize * ysize * 4
+ * bytes each; one set when epf_iters == 0), each part 256-byte aligned. */
 size_t jxlr_workspace_bytes(const jxlr_frame_params* p);
 
 /* The whole path for one frame: reconstruct, epf_iters EPF passes, Gaborish
@@ -166,20 +166,33 @@ jxlr_status jxlr_decode(jxlr_ctx* ctx, const jxlr_frame_params* p, const jxlr_fr
 /* ---- stage entry points (the pieces jxlr_decode runs, for testing and for
  * callers that keep XYB) --------------------------------------------------
  * XYB planes are float [3][ysize][xsize] with row stride xyb_stride elements,
- * plane c at xyb + c * ysize * xyb_stride. */
+ * plane c at xyb + c * ysize * xyb_stride.  `info` is the block-info map,
+ * uint8 [Hb][Wb] (row stride Wb) in device memory owned by the caller. */
+
+/* C.5.4: walks io->strategy (DctSelect) in raster order per 32x32 region and
+ * writes, per 8x8 block, its varblock's transform type (bits 0-3) and the
+ * block's column and row offset inside the varblock (bits 4-5, 6-7).  Every
+ * block of a region with an ill-formed entry (unsupported type, misaligned,
+ * out of bounds, overlapping) is written 0xFF and the sticky device flag is
+ * set. */
+jxlr_status jxlr_block_info(jxlr_ctx* ctx, const jxlr_frame_params* p, const jxlr_frame_io* io,
+                            uint8_t* info, hipStream_t stream);
 
 /* F.2, F.3, Annex G, I.2.7, I.2.4 and the crop of 6.2: coefficient planes of
- * io -> XYB samples. io->out and io->sharpness are not used. */
+ * io -> XYB samples, with the varblocks of `info`.  io->out and
+ * io->sharpness are not used.  Regions marked ill-formed are written as 0. */
 jxlr_status jxlr_reconstruct(jxlr_ctx* ctx, const jxlr_frame_params* p, const jxlr_frame_io* io,
-                             float* xyb, size_t xyb_stride, hipStream_t stream);
+                             const uint8_t* info, float* xyb, size_t xyb_stride,
+                             hipStream_t stream);
 
 /* One edge-preserving filter pass (J.2), xyb_in -> xyb_out (distinct buffers).
- * Uses io->strategy, qf_minus_1, sharpness.  Optional debug outputs (NULL to
- * skip): guide bytes uint8 [3][ysize][xsize] (J.2.2) and sigma int32 [Hb][Wb]
- * (J.2.4) of this pass. */
+ * Uses `info`, io->qf_minus_1 and io->sharpness.  Optional debug outputs
+ * (NULL to skip): guide bytes uint8 [3][ysize][xsize] (J.2.2) and sigma int32
+ * [Hb][Wb] (J.2.4) of this pass.  Pixels of ill-formed regions pass through. */
 jxlr_status jxlr_epf_pass(jxlr_ctx* ctx, const jxlr_frame_params* p, const jxlr_frame_io* io,
-                          const float* xyb_in, float* xyb_out, size_t xyb_stride,
-                          uint8_t* guide_dbg, int32_t* sigma_dbg, hipStream_t stream);
+                          const uint8_t* info, const float* xyb_in, float* xyb_out,
+                          size_t xyb_stride, uint8_t* guide_dbg, int32_t* sigma_dbg,
+                          hipStream_t stream);
 
 /* Gaborish (J.4, when p->gab) and XYB -> RGB (L.2) into io->out in
  * p->out_format. */

@@ -6,6 +6,7 @@ the device code; they are not needed and have been unreliable here.
 """
 import os
 import subprocess
+import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
@@ -16,6 +17,9 @@ ARCH = os.environ.get("JXLR_OFFLOAD_ARCH", "gfx950")
 
 
 def build(verbose: bool = False) -> str:
+    sys.path.insert(0, CSRC)
+    import gen_dct_consts
+    gen_dct_consts.generate()
     cmd = ["/opt/rocm/bin/hipcc", f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
            "-shared", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
            "-I", os.path.join(ROOT, "include"), "-Wall", "-Wno-unused-result",

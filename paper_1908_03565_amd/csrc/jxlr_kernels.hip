@@ -21,6 +21,7 @@
 #include <vector>
 
 #include "../../include/jxlr.h"
+#include "dct_consts.h"
 #include "jxlr_tables.h"
 
 using jxlr::DeviceTables;
@@ -37,12 +38,19 @@ constexpr int kThreads = 256;
 constexpr uint8_t kAbsent = 0xFF;
 
 // Varblock size in blocks of transform type s (I.2.5): "DCT N x M" is N wide.
+// One nibble per type, types 0..11; branch-free on the device.
 __host__ __device__ constexpr int vb_bx(int s) {
-  return (s == 4 || s == 6 || s == 11) ? 2 : (s == 5 || s == 8 || s == 10) ? 4 : 1;
+  return int((0x241412421111ull >> (4 * (s & 15))) & 0xFu);
 }
 __host__ __device__ constexpr int vb_by(int s) {
-  return (s == 4 || s == 7 || s == 10) ? 2 : (s == 5 || s == 9 || s == 11) ? 4 : 1;
+  return int((0x424121421111ull >> (4 * (s & 15))) & 0xFu);
 }
+static_assert(vb_bx(4) == 2 && vb_by(4) == 2 && vb_bx(5) == 4 && vb_by(5) == 4 &&
+                  vb_bx(6) == 2 && vb_by(6) == 1 && vb_bx(7) == 1 && vb_by(7) == 2 &&
+                  vb_bx(8) == 4 && vb_by(8) == 1 && vb_bx(9) == 1 && vb_by(9) == 4 &&
+                  vb_bx(10) == 4 && vb_by(10) == 2 && vb_bx(11) == 2 && vb_by(11) == 4 &&
+                  vb_bx(3) == 1 && vb_by(0) == 1,
+              "varblock sizes of the C.5.4 table");
 // Offset of type s inside DeviceTables::dq.
 __host__ __device__ constexpr int dq_off(int s) {
   int off = 0;
@@ -50,6 +58,8 @@ __host__ __device__ constexpr int dq_off(int s) {
   return off;
 }
 static_assert(dq_off(jxlr::kNumStrategies) == jxlr::kDqFloats, "dequant table layout");
+static_assert(dq_off(5) == 8 * 192 && dq_off(6) == 24 * 192 && dq_off(11) == 44 * 192,
+              "packed offsets of dq_off_lut");
 
 __device__ inline int mirror(int c, int size) {
   // 6.5: reflect with the edge sample repeated, as often as needed
@@ -57,66 +67,85 @@ __device__ inline int mirror(int c, int size) {
   return c;
 }
 
-// Raster scan of the blocks of one region (C.5.4).  nbx, nby: blocks of the
-// region inside the frame.  raw: DctSelect values; owner/strat: per block the
-// index of its varblock's top-left block and the type, kAbsent outside.
-__device__ bool scan_region(const uint8_t* raw, int nbx, int nby, uint8_t* owner,
-                            uint8_t* strat) {
-  for (int i = 0; i < 16; ++i) owner[i] = strat[i] = kAbsent;
-  for (int by = 0; by < nby; ++by)
-    for (int bx = 0; bx < nbx; ++bx) {
-      const int i = by * 4 + bx;
-      if (owner[i] != kAbsent) continue;
-      const int s = raw[i];
-      if (s >= jxlr::kNumStrategies) return false;
-      const int cx = vb_bx(s), cy = vb_by(s);
-      // regions start at multiples of 4 blocks, so local alignment is global
-      if ((bx % cx) || (by % cy) || bx + cx > nbx || by + cy > nby) return false;
-      for (int j = 0; j < cy; ++j)
-        for (int k = 0; k < cx; ++k) {
-          const int m = (by + j) * 4 + bx + k;
-          if (owner[m] != kAbsent) return false;
-          owner[m] = uint8_t(i);
-          strat[m] = uint8_t(s);
-        }
-    }
-  return true;
-}
+// Per-block varblock information, one byte per 8x8 block ([Hb][Wb]):
+// bits 0-3 the transform type, bits 4-5 and 6-7 the block's column and row
+// offset inside its varblock; kInvalid for every block of a region whose
+// DctSelect entries are ill-formed.
+constexpr uint8_t kInvalid = 0xFF;
 
-struct ReconArgs {
-  int W, H, Wb, Hb;
-  const int32_t* ac[3];
-  size_t ac_stride;
-  const int32_t* dc[3];
-  size_t dc_stride;
+struct InfoArgs {
+  int Wb, Hb;
   const uint8_t* strategy;
-  const uint8_t* qf;
   size_t map_stride;
-  const float* cfl_kx;
-  const float* cfl_kb;
-  size_t cfl_stride;
-  float dc_mul[3];  // already divided by 2^extra_levels
-  float kx_dc, kb_dc;
-  float gscale;     // global_scale as float (exact)
-  float one_bias[3];
-  float* xyb;
-  size_t xyb_stride;
+  uint8_t* info;
   int* status;
-  const DeviceTables* __restrict__ tab;
 };
 
-// y = M x for an N-vector strided through LDS, in place (M row-major [n][k]).
-template <int N>
-__device__ inline void lds_transform(const float* __restrict__ M, float* v, int stride) {
-  float in[N];
+// C.5.4 raster scan of one 32x32 region (4x4 blocks) per thread.  At every
+// block not yet covered, the DctSelect value names the varblock whose
+// top-left it is; the varblock must be naturally aligned, inside the frame and
+// disjoint from earlier ones.  Regions start at multiples of 4 blocks and
+// varblocks are at most 4x4 blocks, so a region is scanned on its own.
+// Coverage is a 16-bit mask in registers.
+__global__ __launch_bounds__(kThreads) void blockinfo_kernel(InfoArgs a) {
+  const int Rw = (a.Wb + 3) / 4, Rh = (a.Hb + 3) / 4;
+  const int rid = blockIdx.x * kThreads + threadIdx.x;
+  if (rid >= Rw * Rh) return;
+  const int gbx0 = 4 * (rid % Rw), gby0 = 4 * (rid / Rw);
+  const int nbx = min(4, a.Wb - gbx0), nby = min(4, a.Hb - gby0);
+  uint32_t raw[16], info[16];
 #pragma unroll
-  for (int k = 0; k < N; ++k) in[k] = v[k * stride];
-  for (int n = 0; n < N; ++n) {
-    float acc = 0.0f;
-#pragma unroll
-    for (int k = 0; k < N; ++k) acc = fmaf(M[n * N + k], in[k], acc);
-    v[n * stride] = acc;
+  for (int i = 0; i < 16; ++i) {
+    const int bx = i & 3, by = i >> 2;
+    raw[i] = (bx < nbx && by < nby) ? a.strategy[size_t(gby0 + by) * a.map_stride + gbx0 + bx] : 0u;
+    info[i] = kInvalid;
   }
+  uint32_t covered = 0;
+  bool ok = true;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const int bx = i & 3, by = i >> 2;
+    if (!ok || bx >= nbx || by >= nby || ((covered >> i) & 1u)) continue;
+    const int s = int(raw[i]);
+    if (s >= jxlr::kNumStrategies) { ok = false; continue; }
+    const int cx = vb_bx(s), cy = vb_by(s);
+    if ((bx % cx) || (by % cy) || bx + cx > nbx || by + cy > nby) { ok = false; continue; }
+    const uint32_t row = ((1u << cx) - 1u) << bx;
+    uint32_t m = 0;
+    for (int j = 0; j < cy; ++j) m |= row << (4 * (by + j));
+    if (m & covered) { ok = false; continue; }
+    covered |= m;
+#pragma unroll
+    for (int j = 0; j < 16; ++j)
+      if ((m >> j) & 1u) info[j] = uint32_t(s) | uint32_t((j & 3) - bx) << 4 | uint32_t((j >> 2) - by) << 6;
+  }
+  if (!ok) atomicOr(a.status, 1);
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const int bx = i & 3, by = i >> 2;
+    if (bx < nbx && by < nby) a.info[size_t(gby0 + by) * a.Wb + gbx0 + bx] = ok ? uint8_t(info[i]) : kInvalid;
+  }
+}
+
+// Loads the info bytes of a tile's two regions (blocks b = row * 8 + column,
+// region r = column / 4) into per-region type / owner arrays; owner = index
+// (row * 4 + column) of the varblock's top-left block inside its region.  A
+// region with an ill-formed map, and blocks outside the frame, get kAbsent.
+// Called by threads 0..31; region validity is combined by the caller.
+__device__ inline void load_tile_info(const uint8_t* info, int Wb, int Hb, int gbx0, int gby0,
+                                      int tid, uint8_t (*strat)[16], uint8_t (*owner)[16],
+                                      int* bad) {
+  const int bxl = tid & 7, byl = tid >> 3;
+  const int r = bxl >> 2, lb = byl * 4 + (bxl & 3);
+  const int bx = gbx0 + bxl, by = gby0 + byl;
+  const bool in = bx < Wb && by < Hb;
+  const uint32_t v = info[in ? size_t(by) * Wb + bx : 0];  // (0, 0) stands in outside
+  if (in && v == kInvalid) bad[r] = 1;
+  const bool use = in && v != kInvalid;
+  const uint8_t st = use ? uint8_t(v & 15u) : kAbsent;
+  const uint8_t ow = use ? uint8_t(lb - int((v >> 6) & 3u) * 4 - int((v >> 4) & 3u)) : kAbsent;
+  strat[r][lb] = st;
+  owner[r][lb] = ow;
 }
 
 // AuxIDCT2x2(block, S) of I.2.4.2 on an 8x8 register block.
@@ -175,108 +204,271 @@ __device__ inline void identity_inverse(float (&v)[64]) {
     }
 }
 
-__global__ __launch_bounds__(kThreads) void recon_kernel(ReconArgs a) {
-  __shared__ float coef[3][32][33];
-  __shared__ float s_dc[3][16];
-  __shared__ float s_acmul[16];
-  __shared__ uint8_t s_raw[16], s_owner[16], s_strat[16];
-  __shared__ int s_ok;
+struct ReconArgs {
+  int W, H, Wb, Hb;
+  const int32_t* ac[3];
+  size_t ac_stride;
+  const int32_t* dc[3];
+  size_t dc_stride;
+  const uint8_t* info;
+  const uint8_t* qf;
+  size_t map_stride;
+  const float* cfl_kx;
+  const float* cfl_kb;
+  size_t cfl_stride;
+  float dc_mul[3];  // already divided by 2^extra_levels
+  float kx_dc, kb_dc;
+  float gscale;     // global_scale as float (exact)
+  float one_bias[3];
+  float* xyb;
+  size_t xyb_stride;
+  int* status;
+  const DeviceTables* __restrict__ tab;
+};
+
+// Plain N-point DCT-III in registers, y_n = sum_k x_k cos(pi (2n + 1) k / (2N)),
+// by even/odd splitting: the even inputs form an N/2-point DCT-III, the odd
+// ones a dense N/2 x N/2 product with kOddN; then y_n = e_n + o_n and
+// y_{N-1-n} = e_n - o_n.  x is read and written with a compile-time stride.
+template <int N>
+struct Dct3 {
+  template <typename Acc>
+  __device__ static inline void run(Acc&& x) {
+    constexpr int h = N / 2;
+    float e[h], o[h];
+#pragma unroll
+    for (int m = 0; m < h; ++m) e[m] = x(2 * m);
+    Dct3<h>::run([&](int i) -> float& { return e[i]; });
+#pragma unroll
+    for (int n = 0; n < h; ++n) {
+      float acc = 0.0f;
+#pragma unroll
+      for (int m = 0; m < h; ++m) acc = fmaf(odd(n, m), x(2 * m + 1), acc);
+      o[n] = acc;
+    }
+#pragma unroll
+    for (int n = 0; n < h; ++n) {
+      x(n) = e[n] + o[n];
+      x(N - 1 - n) = e[n] - o[n];
+    }
+  }
+  __device__ static constexpr float odd(int n, int m) {
+    if constexpr (N == 2) return kOdd2[n][m];
+    else if constexpr (N == 4) return kOdd4[n][m];
+    else if constexpr (N == 8) return kOdd8[n][m];
+    else if constexpr (N == 16) return kOdd16[n][m];
+    else return kOdd32[n][m];
+  }
+};
+template <>
+struct Dct3<1> {
+  template <typename Acc>
+  __device__ static inline void run(Acc&&) {}
+};
+
+// One varblock segment of length N in LDS (stride `st` floats), in place.
+template <int N>
+__device__ inline void segment_dct(float* v, int st) {
+  float r[N];
+#pragma unroll
+  for (int k = 0; k < N; ++k) r[k] = v[k * st];
+  Dct3<N>::run([&](int i) -> float& { return r[i]; });
+#pragma unroll
+  for (int k = 0; k < N; ++k) v[k * st] = r[k];
+}
+
+// DCT4 (I.2.4.3) along one axis of an 8-sample segment: the even and the odd
+// positions are two interleaved 4-point transforms whose outputs fill the
+// first and the second half.
+__device__ inline void segment_dct4(float* v, int st) {
+  float a[4], b[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    a[k] = v[(2 * k) * st];
+    b[k] = v[(2 * k + 1) * st];
+  }
+  Dct3<4>::run([&](int i) -> float& { return a[i]; });
+  Dct3<4>::run([&](int i) -> float& { return b[i]; });
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    v[k * st] = a[k];
+    v[(4 + k) * st] = b[k];
+  }
+}
+
+// The column or row segment that starts at `v`: one varblock dimension of n
+// samples of type s.
+__device__ inline void segment(float* v, int st, int s, int n) {
+  if (s == 3) segment_dct4(v, st);
+  else if (n == 8) segment_dct<8>(v, st);
+  else if (n == 16) segment_dct<16>(v, st);
+  else segment_dct<32>(v, st);
+}
+
+constexpr int kRecThreads = 192;     // three wave64s
+constexpr int kRecTW = 64, kRecTH = 32;  // two 32x32 regions side by side
+constexpr int kRecLd = kRecTW + 1;
+
+// Offset of type s inside DeviceTables::dq / dqs, as dq_off, from a byte
+// table packed in two integers (units of 192 floats: three channels of 64).
+__device__ inline int dq_off_lut(int s) {
+  constexpr uint64_t lo = 0x1A18080403020100ull;  // types 0..7: 0 1 2 3 4 8 24 26
+  constexpr uint32_t hi = 0x2C24201Cu;            // types 8..11: 28 32 36 44
+  const uint32_t v = s < 8 ? uint32_t(lo >> (8 * s)) : (hi >> (8 * (s - 8)));
+  return int(v & 0xFFu) * 192;
+}
+
+__global__ __launch_bounds__(kRecThreads) void recon_kernel(ReconArgs a) {
+  __shared__ float coef[3][kRecTH][kRecLd];
+  // DC samples per tile block (b = row * 8 + column), zero-padded so that a
+  // fixed 4x4 window starting at any block stays inside the array.
+  __shared__ float s_dc[3][64];
+  __shared__ float s_acmul[32];
+  // LLF-from-DC axis weights for 1, 2 and 4 DC samples, zero-padded to 4x4.
+  __shared__ float s_llw[3][4][4];
+  __shared__ uint8_t s_owner[2][16], s_strat[2][16];
+  __shared__ int s_bad[2];
 
   const int tid = threadIdx.x;
-  const int gbx0 = 4 * blockIdx.x, gby0 = 4 * blockIdx.y;
-  const int nbx = min(4, a.Wb - gbx0), nby = min(4, a.Hb - gby0);
-  const int gx0 = 8 * gbx0, gy0 = 8 * gby0;
+  const int wave = tid >> 6, lane = tid & 63;
+  const int x0 = kRecTW * blockIdx.x, y0 = kRecTH * blockIdx.y;
+  const int gbx0 = x0 / 8, gby0 = y0 / 8;
   const DeviceTables* __restrict__ T = a.tab;
 
-  if (tid < 16) {
-    const int bx = tid & 3, by = tid >> 2;
-    const bool in = bx < nbx && by < nby;
-    const size_t m = size_t(gby0 + by) * a.map_stride + gbx0 + bx;
-    s_raw[tid] = in ? a.strategy[m] : kAbsent;
+  if (tid < 2) s_bad[tid] = 0;
+  if (tid >= 64 && tid < 112) {
+    const int k = tid - 64, sz = k >> 4, x = (k >> 2) & 3, i = k & 3;
+    float w = 0.0f;
+    if (sz == 0) w = (x == 0 && i == 0) ? 1.0f : 0.0f;
+    else if (sz == 1) w = (x < 2 && i < 2) ? T->a16s[x * 2 + i] : 0.0f;
+    else w = T->a32s[x * 4 + i];
+    s_llw[sz][x][i] = w;
+  }
+  if (tid >= 128 && tid < 128 + 96) {
+    const int k = tid - 128;
+    s_dc[k / 32][32 + (k & 31)] = 0.0f;
+  }
+  __syncthreads();
+  // Blocks of the tile: b = row * 8 + column; region r = column / 4.
+  if (tid < 32) {
+    load_tile_info(a.info, a.Wb, a.Hb, gbx0, gby0, tid, s_strat, s_owner, s_bad);
+    const int bxl = tid & 7, byl = tid >> 3;
+    const int bx = gbx0 + bxl, by = gby0 + byl;
+    const bool in = bx < a.Wb && by < a.Hb;
+    // blocks outside the frame read block (0, 0) and are discarded
+    const size_t m = in ? size_t(by) * a.map_stride + bx : 0;
+    const size_t d = in ? size_t(by) * a.dc_stride + bx : 0;
+    const float dv0 = float(a.dc[0][d]), dv1 = float(a.dc[1][d]), dv2 = float(a.dc[2][d]);
+    const float qfv = float(1 + a.qf[m]);
+    const float x_ = a.dc_mul[0] * dv0, y_ = a.dc_mul[1] * dv1, b_ = a.dc_mul[2] * dv2;
     // C.5.5: AcMul = 2^16 / (global_scale * (1 + dv)); the product is an
     // integer below 2^24, so one rounding.
-    s_acmul[tid] = in ? 65536.0f / (a.gscale * float(1 + a.qf[m])) : 0.0f;
-    for (int c = 0; c < 3; ++c)
-      s_dc[c][tid] =
-          in ? a.dc_mul[c] * float(a.dc[c][size_t(gby0 + by) * a.dc_stride + gbx0 + bx]) : 0.0f;
+    s_acmul[tid] = in ? 65536.0f / (a.gscale * qfv) : 0.0f;
+    // Annex G on the DC samples, with the DC factors
+    s_dc[0][tid] = in ? fmaf(a.kx_dc, y_, x_) : 0.0f;
+    s_dc[1][tid] = in ? y_ : 0.0f;
+    s_dc[2][tid] = in ? fmaf(a.kb_dc, y_, b_) : 0.0f;
   }
   __syncthreads();
-  if (tid == 0) s_ok = scan_region(s_raw, nbx, nby, s_owner, s_strat);
-  if (tid < 16) {  // Annex G on the DC samples, with the DC factors
-    const float y = s_dc[1][tid];
-    s_dc[0][tid] = fmaf(a.kx_dc, y, s_dc[0][tid]);
-    s_dc[2][tid] = fmaf(a.kb_dc, y, s_dc[2][tid]);
+  if (tid < 2 && s_bad[tid]) {
+    for (int i = 0; i < 16; ++i) s_strat[tid][i] = kAbsent;
   }
   __syncthreads();
-  if (!s_ok) {
-    if (tid == 0) atomicOr(a.status, 1);
-    for (int p = tid; p < 1024; p += kThreads) {
-      const int gx = gx0 + (p & 31), gy = gy0 + (p >> 5);
-      if (gx < a.W && gy < a.H)
-        for (int c = 0; c < 3; ++c) a.xyb[(size_t(c) * a.H + gy) * a.xyb_stride + gx] = 0.0f;
-    }
-    return;
-  }
 
-  // The region's 64x64 chroma-from-luma tile.
-  const size_t tile = size_t(gy0 / 64) * a.cfl_stride + gx0 / 64;
-  const float kx = a.cfl_kx[tile], kb = a.cfl_kb[tile];
-
-  // Dequantization (F.3), LLF from DC (I.2.7), chroma from luma (Annex G).
-  for (int j = 0; j < 4; ++j) {
-    const int p = tid + kThreads * j;
-    const int py = p >> 5, px = p & 31;
-    const int lb = (py >> 3) * 4 + (px >> 3);
-    const int s = s_strat[lb];
-    if (s == kAbsent) continue;
-    const int o = s_owner[lb];
-    const int x = px - 8 * (o & 3), y = py - 8 * (o >> 2);
-    const int cxb = vb_bx(s), cyb = vb_by(s);
-    float K[3];
-    if (x < cxb && y < cyb) {
-      const float* ax = cxb == 2 ? T->a16 : T->a32;
-      const float* ay = cyb == 2 ? T->a16 : T->a32;
+  // F.3 dequantization, I.2.7 LLF from DC, Annex G chroma from luma; the
+  // tables carry the transform scales (the passes below are plain DCT-III).
+  // Wave w takes tile rows w, w + 3, ... (11 rows at most); lane = tile
+  // column.  All global loads of the lane's rows are issued before any
+  // arithmetic; rows outside the frame or in ill-formed regions load the
+  // tile's first coefficient and are not stored.
+  {
+    constexpr int kRows = 11;
+    const int X = lane, r = X >> 5, bxl = X >> 3;
+    const size_t tile = size_t(y0 / 64) * a.cfl_stride + x0 / 64;
+    const float kx = a.cfl_kx[tile], kb = a.cfl_kb[tile];
+    int rs[kRows], ro[kRows], rdq[kRows];
+    int q[kRows][3];
+    float dqv[kRows][3];
+#pragma unroll
+    for (int k = 0; k < kRows; ++k) {
+      const int Y = min(wave + 3 * k, kRecTH - 1);
+      const int lb = (Y >> 3) * 4 + (bxl & 3);
+      int s = s_strat[r][lb];
+      if (wave + 3 * k >= kRecTH) s = kAbsent;
+      const int o = s_owner[r][lb];
+      const int x = (X & 31) - 8 * (o & 3), y = Y - 8 * (o >> 2);
+      const bool hf = s != kAbsent && !(x < vb_bx(s) && y < vb_by(s));
+      const int sz = 64 * vb_bx(s) * vb_by(s);
+      rs[k] = s;
+      ro[k] = o;
+      rdq[k] = hf ? dq_off_lut(s) + y * 8 * vb_bx(s) + x : 0;
+      const size_t g = hf ? size_t(y0 + Y) * a.ac_stride + x0 + X : size_t(y0) * a.ac_stride + x0;
+#pragma unroll
       for (int c = 0; c < 3; ++c) {
-        float acc = 0.0f;
-        for (int jy = 0; jy < cyb; ++jy) {
-          const float fy = cyb == 1 ? 1.0f : ay[y * cyb + jy];
-          for (int ix = 0; ix < cxb; ++ix) {
-            const float fx = cxb == 1 ? 1.0f : ax[x * cxb + ix];
-            acc = fmaf(fy * fx, s_dc[c][o + 4 * jy + ix], acc);
-          }
+        q[k][c] = a.ac[c][g];
+        dqv[k][c] = T->dqs[rdq[k] + (hf ? c * sz : 0)];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < kRows; ++k) {
+      const int Y = wave + 3 * k;
+      const int s = rs[k];
+      if (s == kAbsent) continue;
+      const int o = ro[k];
+      const int ob = (o >> 2) * 8 + 4 * r + (o & 3);  // the varblock's top-left tile block
+      const int x = (X & 31) - 8 * (o & 3), y = Y - 8 * (o >> 2);
+      const int cxb = vb_bx(s), cyb = vb_by(s);
+      float K[3];
+      if (x < cxb && y < cyb) {
+        const int sx = cxb == 4 ? 2 : cxb - 1, sy = cyb == 4 ? 2 : cyb - 1;
+        float fx[4], fy[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          fx[i] = s_llw[sx][x][i];
+          fy[i] = s_llw[sy][y][i];
         }
-        K[c] = acc;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          float acc = 0.0f;
+#pragma unroll
+          for (int jy = 0; jy < 4; ++jy) {
+            float row = 0.0f;
+#pragma unroll
+            for (int ix = 0; ix < 4; ++ix) row = fmaf(fx[ix], s_dc[c][ob + 8 * jy + ix], row);
+            acc = fmaf(fy[jy], row, acc);
+          }
+          K[c] = acc;
+        }
+      } else {
+        const float acm = s_acmul[ob];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const int qq = q[k][c];
+          const float fq = float(qq);
+          const float bq = (qq >= -1 && qq <= 1) ? fq * a.one_bias[c] : fq - 0.145f / fq;
+          K[c] = bq * acm * dqv[k][c];
+        }
+        K[0] = fmaf(kx, K[1], K[0]);
+        K[2] = fmaf(kb, K[1], K[2]);
       }
-    } else {
-      const size_t g = size_t(gy0 + py) * a.ac_stride + gx0 + px;
-      const int sz = 64 * cxb * cyb;
-      const float* dq = T->dq + dq_off(s) + y * 8 * cxb + x;
-      const float acm = s_acmul[o];
-      for (int c = 0; c < 3; ++c) {
-        const int q = a.ac[c][g];
-        const float fq = float(q);
-        const float b = (q >= -1 && q <= 1) ? fq * a.one_bias[c] : fq - 0.145f / fq;
-        K[c] = b * acm * dq[c * sz];
-      }
-      K[0] = fmaf(kx, K[1], K[0]);
-      K[2] = fmaf(kb, K[1], K[2]);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) coef[c][Y][X] = K[c];
     }
-    for (int c = 0; c < 3; ++c) coef[c][py][px] = K[c];
   }
   __syncthreads();
 
-  // 8x8 transforms that are not separable matrix products: DCT2 and Identity
-  // entirely, and the 2x2 corner step of DCT4 (I.2.4.2-I.2.4.4).
-  if (tid < 48) {
-    const int lb = tid & 15, c = tid >> 4;
-    const int s = s_strat[lb];
-    if ((s == 1 || s == 2 || s == 3) && s_owner[lb] == lb) {
-      float* base = &coef[c][8 * (lb >> 2)][8 * (lb & 3)];
+  // 8x8 transforms that are not separable products: DCT2 and Identity, and
+  // the 2x2 corner step of DCT4 (I.2.4.2-I.2.4.4).  Wave c: channel c.
+  if (lane < 32) {
+    const int c = wave, r = lane >> 4, lb = lane & 15;
+    const int s = s_strat[r][lb];
+    if (s == 1 || s == 2 || s == 3) {
+      float* base = &coef[c][8 * (lb >> 2)][32 * r + 8 * (lb & 3)];
       float v[64];
 #pragma unroll
-      for (int r = 0; r < 8; ++r)
+      for (int i = 0; i < 8; ++i)
 #pragma unroll
-        for (int q = 0; q < 8; ++q) v[r * 8 + q] = base[r * 33 + q];
+        for (int j = 0; j < 8; ++j) v[i * 8 + j] = base[i * kRecLd + j];
       if (s == 2) {
         aux_idct2x2<2>(v);
         aux_idct2x2<4>(v);
@@ -287,50 +479,49 @@ __global__ __launch_bounds__(kThreads) void recon_kernel(ReconArgs a) {
         aux_idct2x2<2>(v);
       }
 #pragma unroll
-      for (int r = 0; r < 8; ++r)
+      for (int i = 0; i < 8; ++i)
 #pragma unroll
-        for (int q = 0; q < 8; ++q) base[r * 33 + q] = v[r * 8 + q];
+        for (int j = 0; j < 8; ++j) base[i * kRecLd + j] = v[i * 8 + j];
     }
   }
   __syncthreads();
 
-  // Column pass: every column segment of every varblock (S = T_by K T_bx^T).
-  for (int it = tid; it < 384; it += kThreads) {
-    const int c = it >> 7, X = it & 31, br = (it >> 5) & 3;
-    const int lb = br * 4 + (X >> 3);
-    const int s = s_strat[lb];
-    if (s == kAbsent || s == 1 || s == 2 || (s_owner[lb] >> 2) != br) continue;
-    float* v = &coef[c][8 * br][X];
-    const int by = vb_by(s);
-    if (s == 3) lds_transform<8>(T->m4, v, 33);
-    else if (by == 1) lds_transform<8>(T->t8, v, 33);
-    else if (by == 2) lds_transform<16>(T->t16, v, 33);
-    else lds_transform<32>(T->t32, v, 33);
+  // Column pass: lane = tile column, wave = channel; the column's varblock
+  // segments one after the other.
+  {
+    const int c = wave, X = lane, r = X >> 5;
+    for (int br = 0; br < 4; ++br) {
+      const int lb = br * 4 + ((X & 31) >> 3);
+      const int s = s_strat[r][lb];
+      if (s == kAbsent || s == 1 || s == 2 || (s_owner[r][lb] >> 2) != br) continue;
+      segment(&coef[c][8 * br][X], kRecLd, s, 8 * vb_by(s));
+    }
   }
   __syncthreads();
 
-  // Row pass.
-  for (int it = tid; it < 384; it += kThreads) {
-    const int c = it >> 7, Y = it & 31, bc = (it >> 5) & 3;
-    const int lb = (Y >> 3) * 4 + bc;
-    const int s = s_strat[lb];
-    if (s == kAbsent || s == 1 || s == 2 || (s_owner[lb] & 3) != bc) continue;
-    float* v = &coef[c][Y][8 * bc];
-    const int bx = vb_bx(s);
-    if (s == 3) lds_transform<8>(T->m4, v, 1);
-    else if (bx == 1) lds_transform<8>(T->t8, v, 1);
-    else if (bx == 2) lds_transform<16>(T->t16, v, 1);
-    else lds_transform<32>(T->t32, v, 1);
+  // Row pass: lane = (region, row).
+  {
+    const int c = wave, r = lane >> 5, Y = lane & 31;
+    for (int bc = 0; bc < 4; ++bc) {
+      const int lb = (Y >> 3) * 4 + bc;
+      const int s = s_strat[r][lb];
+      if (s == kAbsent || s == 1 || s == 2 || (s_owner[r][lb] & 3) != bc) continue;
+      segment(&coef[c][Y][32 * r + 8 * bc], 1, s, 8 * vb_bx(s));
+    }
   }
   __syncthreads();
 
-  // Crop (6.2) and store.
-  for (int j = 0; j < 4; ++j) {
-    const int p = tid + kThreads * j;
-    const int py = p >> 5, px = p & 31;
-    const int gx = gx0 + px, gy = gy0 + py;
-    if (gx < a.W && gy < a.H)
-      for (int c = 0; c < 3; ++c) a.xyb[(size_t(c) * a.H + gy) * a.xyb_stride + gx] = coef[c][py][px];
+  // Crop (6.2) and store; an ill-formed region is written as zero.
+  {
+    const int X = lane, gx = x0 + X;
+    const bool ok = !s_bad[X >> 5];
+    if (gx < a.W)
+      for (int Y = wave; Y < kRecTH; Y += 3) {
+        const int gy = y0 + Y;
+        if (gy >= a.H) break;
+        for (int c = 0; c < 3; ++c)
+          a.xyb[(size_t(c) * a.H + gy) * a.xyb_stride + gx] = ok ? coef[c][Y][X] : 0.0f;
+      }
   }
 }
 
@@ -352,7 +543,7 @@ __global__ __launch_bounds__(kThreads) void recon_kernel(ReconArgs a) {
 
 struct EpfArgs {
   int W, H, Wb, Hb;
-  const uint8_t* strategy;
+  const uint8_t* info;
   const uint8_t* qf;
   const uint8_t* sharp;
   size_t map_stride;
@@ -389,8 +580,8 @@ __global__ __launch_bounds__(kThreads, 2) void epf_kernel(EpfArgs a) {
   __shared__ uint32_t s_w[3][kPH][kGW + 1];
   __shared__ float s_rng[32];
   __shared__ int s_mul[32];
-  __shared__ uint8_t s_raw[2][16], s_owner[2][16], s_strat[2][16];
-  __shared__ int s_ok[2];
+  __shared__ uint8_t s_owner[2][16], s_strat[2][16];
+  __shared__ int s_bad[2];
 
   const int tid = threadIdx.x;
   const int x0 = kEpfTW * blockIdx.x, y0 = kEpfTH * blockIdx.y;
@@ -422,11 +613,7 @@ __global__ __launch_bounds__(kThreads, 2) void epf_kernel(EpfArgs a) {
     s_w[1][v][g] = w1;
     s_w[2][v][g] = w2;
   }
-  if (tid < 32) {
-    const int r = tid >> 4, lb = tid & 15;
-    const int bx = gbx0 + 4 * r + (lb & 3), by = gby0 + (lb >> 2);
-    s_raw[r][lb] = (bx < a.Wb && by < a.Hb) ? a.strategy[size_t(by) * a.map_stride + bx] : kAbsent;
-  }
+  if (tid < 2) s_bad[tid] = 0;
   __syncthreads();
 
   // B: guide words at every start column; C: region scans.
@@ -436,12 +623,7 @@ __global__ __launch_bounds__(kThreads, 2) void epf_kernel(EpfArgs a) {
     const int v = rem / (kPW - 1), u = rem % (kPW - 1);
     s_p[c][v][u] = __builtin_amdgcn_alignbyte(s_w[c][v][(u >> 2) + 1], s_w[c][v][u >> 2], u & 3);
   }
-  if ((tid & 63) == 0 && tid < 128) {
-    const int r = tid >> 6;
-    // a region right of the frame has no blocks: the scan marks all absent
-    const int nbx = max(0, min(4, a.Wb - (gbx0 + 4 * r))), nby = min(4, a.Hb - gby0);
-    s_ok[r] = scan_region(s_raw[r], nbx, nby, s_owner[r], s_strat[r]);
-  }
+  if (tid < 32) load_tile_info(a.info, a.Wb, a.Hb, gbx0, gby0, tid, s_strat, s_owner, s_bad);
   // Per-block range of `scaled` (J.2.4) over the block's pixels inside the
   // frame: eight lanes per block, one row each, reduced across the lanes.
   {
@@ -476,8 +658,7 @@ __global__ __launch_bounds__(kThreads, 2) void epf_kernel(EpfArgs a) {
     const int r = bxl >> 2, lb = byl * 4 + (bxl & 3);
     const int bx = gbx0 + bxl, by = gby0 + byl;
     int sig = 0;
-    if (!s_ok[r] && lb == 0) atomicOr(a.status, 1);
-    if (s_ok[r] && s_strat[r][lb] != kAbsent) {
+    if (!s_bad[r] && s_strat[r][lb] != kAbsent) {
       float rg = 0.0f;
       for (int m = 0; m < 16; ++m)
         if (s_owner[r][m] == s_owner[r][lb]) rg = fmaxf(rg, s_rng[(m >> 2) * 8 + 4 * r + (m & 3)]);
@@ -790,15 +971,41 @@ jxlr_status jxlr_validate_maps_host(const jxlr_frame_params* p, const uint8_t* s
   return JXLR_OK;
 }
 
+namespace {
+size_t round256(size_t v) { return (v + 255) & ~size_t(255); }
+size_t info_bytes(const jxlr_frame_params* p) {
+  return round256(size_t(blocks_of(p->xsize)) * blocks_of(p->ysize));
+}
+size_t xyb_bytes(const jxlr_frame_params* p) {
+  return round256(size_t(3) * p->xsize * p->ysize * sizeof(float));
+}
+}  // namespace
+
 size_t jxlr_workspace_bytes(const jxlr_frame_params* p) {
   if (check_params(p) != JXLR_OK) return 0;
-  const size_t one = (size_t(3) * p->xsize * p->ysize * sizeof(float) + 255) & ~size_t(255);
-  return p->epf_iters > 0 ? 2 * one : one;
+  return info_bytes(p) + (p->epf_iters > 0 ? 2 : 1) * xyb_bytes(p);
+}
+
+jxlr_status jxlr_block_info(jxlr_ctx* ctx, const jxlr_frame_params* p, const jxlr_frame_io* io,
+                            uint8_t* info, hipStream_t stream) {
+  if (!ctx || !info || !io || !io->strategy) return JXLR_E_NULL;
+  jxlr_status st = check_params(p);
+  if (st) return st;
+  const int Wb = blocks_of(p->xsize), Hb = blocks_of(p->ysize);
+  if (io->map_stride < size_t(Wb)) return JXLR_E_SIZE;
+  InfoArgs a{Wb, Hb, io->strategy, io->map_stride, info, ctx->status};
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return JXLR_E_HIP;
+  const int regions = ((Wb + 3) / 4) * ((Hb + 3) / 4);
+  hipLaunchKernelGGL(blockinfo_kernel, dim3((regions + kThreads - 1) / kThreads), dim3(kThreads), 0,
+                     stream, a);
+  return launch_status(hipGetLastError());
 }
 
 jxlr_status jxlr_reconstruct(jxlr_ctx* ctx, const jxlr_frame_params* p, const jxlr_frame_io* io,
-                             float* xyb, size_t xyb_stride, hipStream_t stream) {
-  if (!ctx || !xyb) return JXLR_E_NULL;
+                             const uint8_t* info, float* xyb, size_t xyb_stride,
+                             hipStream_t stream) {
+  if (!ctx || !xyb || !info) return JXLR_E_NULL;
   jxlr_status st = check_params(p);
   if (st) return st;
   if ((st = check_maps_io(p, io, false))) return st;
@@ -821,7 +1028,7 @@ jxlr_status jxlr_reconstruct(jxlr_ctx* ctx, const jxlr_frame_params* p, const jx
   }
   a.ac_stride = io->ac_stride;
   a.dc_stride = io->dc_stride;
-  a.strategy = io->strategy;
+  a.info = info;
   a.qf = io->qf_minus_1;
   a.map_stride = io->map_stride;
   a.cfl_kx = io->cfl_kx;
@@ -838,15 +1045,15 @@ jxlr_status jxlr_reconstruct(jxlr_ctx* ctx, const jxlr_frame_params* p, const jx
   a.tab = ctx->tables;
   DeviceGuard g(ctx->device);
   if (!g.ok) return JXLR_E_HIP;
-  dim3 grid((Wb + 3) / 4, (Hb + 3) / 4);
-  hipLaunchKernelGGL(recon_kernel, grid, dim3(kThreads), 0, stream, a);
+  dim3 grid((p->xsize + kRecTW - 1) / kRecTW, (p->ysize + kRecTH - 1) / kRecTH);
+  hipLaunchKernelGGL(recon_kernel, grid, dim3(kRecThreads), 0, stream, a);
   return launch_status(hipGetLastError());
 }
 
 jxlr_status jxlr_epf_pass(jxlr_ctx* ctx, const jxlr_frame_params* p, const jxlr_frame_io* io,
-                          const float* in, float* out, size_t stride, uint8_t* guide_dbg,
-                          int32_t* sigma_dbg, hipStream_t stream) {
-  if (!ctx || !in || !out) return JXLR_E_NULL;
+                          const uint8_t* info, const float* in, float* out, size_t stride,
+                          uint8_t* guide_dbg, int32_t* sigma_dbg, hipStream_t stream) {
+  if (!ctx || !in || !out || !info) return JXLR_E_NULL;
   jxlr_status st = check_params(p);
   if (st) return st;
   if ((st = check_maps_io(p, io, true))) return st;
@@ -856,7 +1063,7 @@ jxlr_status jxlr_epf_pass(jxlr_ctx* ctx, const jxlr_frame_params* p, const jxlr_
   a.H = int(p->ysize);
   a.Wb = blocks_of(p->xsize);
   a.Hb = blocks_of(p->ysize);
-  a.strategy = io->strategy;
+  a.info = info;
   a.qf = io->qf_minus_1;
   a.sharp = io->sharpness;
   a.map_stride = io->map_stride;
@@ -936,12 +1143,16 @@ jxlr_status jxlr_decode(jxlr_ctx* ctx, const jxlr_frame_params* p, const jxlr_fr
   if (st) return st;
   const size_t need = jxlr_workspace_bytes(p);
   if (ws_bytes < need) return JXLR_E_WORKSPACE;
-  float* bufa = static_cast<float*>(ws);
-  float* bufb = reinterpret_cast<float*>(static_cast<char*>(ws) + need / 2);
+  char* base = static_cast<char*>(ws);
+  uint8_t* info = reinterpret_cast<uint8_t*>(base);
+  float* bufa = reinterpret_cast<float*>(base + info_bytes(p));
+  float* bufb = reinterpret_cast<float*>(base + info_bytes(p) + xyb_bytes(p));
   const size_t stride = p->xsize;
-  if ((st = jxlr_reconstruct(ctx, p, io, bufa, stride, stream))) return st;
+  if ((st = jxlr_block_info(ctx, p, io, info, stream))) return st;
+  if ((st = jxlr_reconstruct(ctx, p, io, info, bufa, stride, stream))) return st;
   for (int it = 0; it < p->epf_iters; ++it) {
-    if ((st = jxlr_epf_pass(ctx, p, io, bufa, bufb, stride, nullptr, nullptr, stream))) return st;
+    if ((st = jxlr_epf_pass(ctx, p, io, info, bufa, bufb, stride, nullptr, nullptr, stream)))
+      return st;
     std::swap(bufa, bufb);
   }
   return jxlr_finish(ctx, p, io, bufa, stride, stream);

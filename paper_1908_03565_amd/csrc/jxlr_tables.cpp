@@ -221,6 +221,11 @@ bool dequant_matrix_f64(int s, int c, double* out) {
   return true;
 }
 
+double transform_scale(int n, int k) {
+  // T_N[r][k] = q_N[r][k] / I(N, k) and q_N = sqrt(eps_k / N) cos(...)
+  return std::sqrt((k == 0 ? 1.0 : 2.0) / n) / scale_i(n, k);
+}
+
 void inverse_transform_matrix_f64(int n, double* out) {
   for (int r = 0; r < n; ++r)
     for (int k = 0; k < n; ++k) out[r * n + k] = ortho(n, r, k) / scale_i(n, k);
@@ -270,16 +275,27 @@ bool build_tables(DeviceTables* t) {
   // F_n = n diag(I(n, .)) Q_n^T.
   for (int n : {2, 4}) {
     float* a = n == 2 ? t->a16 : t->a32;
+    float* as = n == 2 ? t->a16s : t->a32s;
     for (int x = 0; x < n; ++x)
-      for (int i = 0; i < n; ++i)
-        a[x * n + i] = float(scale_i(n, x) * ortho(n, i, x) * scale_f(n, 8 * n, x));
+      for (int i = 0; i < n; ++i) {
+        const double v = scale_i(n, x) * ortho(n, i, x) * scale_f(n, 8 * n, x);
+        a[x * n + i] = float(v);
+        as[x * n + i] = float(v * transform_scale(8 * n, x));
+      }
   }
   std::vector<double> dq(1024);
   for (int s = 0; s < kNumStrategies; ++s) {
-    const int sz = 64 * blocks_x(s) * blocks_y(s);
+    const int X = 8 * blocks_x(s), Y = 8 * blocks_y(s), sz = X * Y;
     for (int c = 0; c < 3; ++c) {
       if (!dequant_matrix_f64(s, c, dq.data())) return false;
-      for (int i = 0; i < sz; ++i) t->dq[dq_offset(s) + c * sz + i] = float(dq[i]);
+      for (int i = 0; i < sz; ++i) {
+        const int x = i % X, y = i / X;
+        double sc = 1.0;
+        if (s == 3) sc = transform_scale(4, y / 2) * transform_scale(4, x / 2);
+        else if (s != 1 && s != 2) sc = transform_scale(Y, y) * transform_scale(X, x);
+        t->dq[dq_offset(s) + c * sz + i] = float(dq[i]);
+        t->dqs[dq_offset(s) + c * sz + i] = float(dq[i] * sc);
+      }
     }
   }
   for (int shift = 0; shift <= 8; ++shift) epf_mul_table(shift, t->mul_table[shift]);

@@ -43,6 +43,14 @@ struct DeviceTables {
   float a32[4 * 4];
   // Dequantization matrices (C.6.1, defaults of C.6.1.1), row-major [y][x].
   float dq[kDqFloats];
+  // The same matrices multiplied by the per-frequency scales of the inverse
+  // transforms (s_N(y) s_N(x); for DCT4 the 4-point scales of the
+  // interleaved sub-blocks; 1 for DCT2 and Identity), so that the kernels
+  // run the plain DCT-III y_n = sum_k x_k cos(pi (2n + 1) k / (2N)).
+  float dqs[kDqFloats];
+  // a16 / a32 with the same scale applied to the output frequency x.
+  float a16s[2 * 2];
+  float a32s[4 * 4];
   // mul_table of J.2.4 for sigma 0..672 (entries below 16 unused), one per
   // kSigmaShift value 0..8.
   int32_t mul_table[9][673];
@@ -55,6 +63,9 @@ bool build_tables(DeviceTables* t);
 // The same tables in double precision, for the host-side cross-checks.
 bool dequant_matrix_f64(int s, int c, double* out);
 void inverse_transform_matrix_f64(int n, double* out);
+// s_N(k): the draft's inverse transform is the plain DCT-III applied to
+// coefficients multiplied by s_N(k).
+double transform_scale(int n, int k);
 void epf_mul_table(int sigma_shift, int32_t* table);
 
 }  // namespace jxlr

@@ -73,10 +73,13 @@ _SIGS = {
     "jxlr_workspace_bytes": ([C.POINTER(FrameParams)], C.c_size_t),
     "jxlr_decode": ([C.c_void_p, C.POINTER(FrameParams), C.POINTER(FrameIO), C.c_void_p,
                      C.c_size_t, C.c_void_p], C.c_int),
+    "jxlr_block_info": ([C.c_void_p, C.POINTER(FrameParams), C.POINTER(FrameIO), C.c_void_p,
+                         C.c_void_p], C.c_int),
     "jxlr_reconstruct": ([C.c_void_p, C.POINTER(FrameParams), C.POINTER(FrameIO), C.c_void_p,
-                          C.c_size_t, C.c_void_p], C.c_int),
+                          C.c_void_p, C.c_size_t, C.c_void_p], C.c_int),
     "jxlr_epf_pass": ([C.c_void_p, C.POINTER(FrameParams), C.POINTER(FrameIO), C.c_void_p,
-                       C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
+                       C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p, C.c_void_p],
+                      C.c_int),
     "jxlr_finish": ([C.c_void_p, C.POINTER(FrameParams), C.POINTER(FrameIO), C.c_void_p,
                      C.c_size_t, C.c_void_p], C.c_int),
     "jxlr_get_device_status": ([C.c_void_p, C.c_void_p], C.c_int),
@@ -214,18 +217,28 @@ class Context:
         dt = getattr(torch, _OUT_DTYPE[p.out_format])
         return torch.empty((3, p.ysize, p.xsize), dtype=dt, device=f"cuda:{self.device}")
 
+    def empty_info(self, p):
+        import torch
+        return torch.empty(((p.ysize + 7) // 8, (p.xsize + 7) // 8), dtype=torch.uint8,
+                           device=f"cuda:{self.device}")
+
     def workspace(self, p):
         import torch
         return torch.empty(workspace_bytes(p), dtype=torch.uint8, device=f"cuda:{self.device}")
 
     # --- entry points ---
-    def reconstruct(self, p, df, xyb, stream=None):
-        _check(lib().jxlr_reconstruct(self.handle, C.byref(p), C.byref(df.io()), xyb.data_ptr(),
-                                      xyb.shape[2], _stream_handle(stream)), "reconstruct")
+    def block_info(self, p, df, info, stream=None):
+        _check(lib().jxlr_block_info(self.handle, C.byref(p), C.byref(df.io()), info.data_ptr(),
+                                     _stream_handle(stream)), "block_info")
 
-    def epf_pass(self, p, df, xyb_in, xyb_out, guide=None, sigma=None, stream=None):
-        _check(lib().jxlr_epf_pass(self.handle, C.byref(p), C.byref(df.io()), xyb_in.data_ptr(),
-                                   xyb_out.data_ptr(), xyb_in.shape[2],
+    def reconstruct(self, p, df, info, xyb, stream=None):
+        _check(lib().jxlr_reconstruct(self.handle, C.byref(p), C.byref(df.io()), info.data_ptr(),
+                                      xyb.data_ptr(), xyb.shape[2], _stream_handle(stream)),
+               "reconstruct")
+
+    def epf_pass(self, p, df, info, xyb_in, xyb_out, guide=None, sigma=None, stream=None):
+        _check(lib().jxlr_epf_pass(self.handle, C.byref(p), C.byref(df.io()), info.data_ptr(),
+                                   xyb_in.data_ptr(), xyb_out.data_ptr(), xyb_in.shape[2],
                                    guide.data_ptr() if guide is not None else None,
                                    sigma.data_ptr() if sigma is not None else None,
                                    _stream_handle(stream)), "epf_pass")

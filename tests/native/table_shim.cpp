@@ -19,6 +19,9 @@ const float* shim_m4() { return g_tables.m4; }
 const float* shim_a16() { return g_tables.a16; }
 const float* shim_a32() { return g_tables.a32; }
 const float* shim_dq() { return g_tables.dq; }
+const float* shim_dqs() { return g_tables.dqs; }
+const float* shim_a16s() { return g_tables.a16s; }
+const float* shim_a32s() { return g_tables.a32s; }
 const int32_t* shim_mul(int shift) { return g_tables.mul_table[shift]; }
 int shim_dq_offset(int s) { return jxlr::dq_offset(s); }
 }

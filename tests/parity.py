@@ -63,8 +63,10 @@ def affected_mask(p, gpu_passes, orc_passes):
 def gpu_stages(ctx, p, df):
     """Runs the stage entry points; returns numpy arrays of every stage."""
     import torch
+    info = ctx.empty_info(p)
+    ctx.block_info(p, df, info)
     xyb = ctx.empty_xyb(p)
-    ctx.reconstruct(p, df, xyb)
+    ctx.reconstruct(p, df, info, xyb)
     res = {"recon": xyb.cpu().numpy(), "epf": []}
     Hb, Wb = (p.ysize + 7) // 8, (p.xsize + 7) // 8
     cur = xyb
@@ -72,7 +74,7 @@ def gpu_stages(ctx, p, df):
         nxt = ctx.empty_xyb(p)
         guide = torch.empty((3, p.ysize, p.xsize), dtype=torch.uint8, device=cur.device)
         sigma = torch.empty((Hb, Wb), dtype=torch.int32, device=cur.device)
-        ctx.epf_pass(p, df, cur, nxt, guide, sigma)
+        ctx.epf_pass(p, df, info, cur, nxt, guide, sigma)
         res["epf"].append((nxt.cpu().numpy(), guide.cpu().numpy(), sigma.cpu().numpy()))
         cur = nxt
     out = ctx.empty_out(p)

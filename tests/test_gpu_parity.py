@@ -153,8 +153,10 @@ def test_dc_only_frame_is_constant_per_varblock(ctx):
     f["dc"] = np.ascontiguousarray(f["dc"][:, ty, tx])  # top-left DC everywhere
     p = J.params(160, 96, **f["params"])
     df = J.DeviceFrame(f)
+    info = ctx.empty_info(p)
+    ctx.block_info(p, df, info)
     xyb = ctx.empty_xyb(p)
-    ctx.reconstruct(p, df, xyb)
+    ctx.reconstruct(p, df, info, xyb)
     x = xyb.cpu().numpy()
     q = O.params(160, 96, **f["params"])
     np.testing.assert_allclose(x, O.reconstruct(q, f), atol=XYB_TOL)
@@ -184,8 +186,10 @@ def test_ill_formed_map_sets_device_flag(ctx):
     assert J.validate_maps_host(p, f) == 4
     assert ctx.device_status() == 0
     df = J.DeviceFrame(f)
+    info = ctx.empty_info(p)
+    ctx.block_info(p, df, info)
     xyb = ctx.empty_xyb(p)
-    ctx.reconstruct(p, df, xyb)
+    ctx.reconstruct(p, df, info, xyb)
     assert ctx.device_status() == 10
     assert ctx.device_status() == 0  # the flag is cleared by reading it
     x = xyb.cpu().numpy()
