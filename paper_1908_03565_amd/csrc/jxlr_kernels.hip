@@ -588,40 +588,67 @@ __global__ __launch_bounds__(kThreads, 2) void epf_kernel(EpfArgs a) {
   const int gbx0 = x0 / 8, gby0 = y0 / 8;
   const size_t plane = size_t(a.H) * a.stride;
 
-  // A: input samples and packed guide words (4 columns per word).
+  // A: input samples and packed guide words (4 columns per word).  Tiles
+  // whose halo lies inside the frame skip the mirroring and, with a row
+  // stride that keeps 16-byte alignment, load four columns at once.
+  const bool interior = x0 >= 4 && x0 + 4 * kGW - 4 <= a.W && y0 >= 4 && y0 + kPH - 4 <= a.H;
+  const bool vec = interior && (a.stride & 3) == 0 && (reinterpret_cast<uintptr_t>(a.in) & 15) == 0;
   for (int it = tid; it < kPH * kGW; it += kThreads) {
     const int v = it / kGW, g = it % kGW;
-    const int gy = mirror(y0 - 4 + v, a.H);
-    uint32_t w0 = 0, w1 = 0, w2 = 0;
+    const int gy = interior ? y0 - 4 + v : mirror(y0 - 4 + v, a.H);
+    float vals[3][4];
+    if (vec) {
+      const float* p = a.in + size_t(gy) * a.stride + (x0 - 4 + 4 * g);
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int lxx = x0 - 4 + 4 * g + j;
-      const int gx = mirror(lxx, a.W);
-      const float* p = a.in + size_t(gy) * a.stride + gx;
-      const float v0 = p[0], v1 = p[plane], v2 = p[2 * plane];
-      w0 |= guide_byte(v0, a.minv[0], a.scale[0]) << (8 * j);
-      w1 |= guide_byte(v1, a.minv[1], a.scale[1]) << (8 * j);
-      w2 |= guide_byte(v2, a.minv[2], a.scale[2]) << (8 * j);
-      const int ci = 4 * g + j - 1, ri = v - 1;
-      if (ci >= 0 && ci < kInW && ri >= 0 && ri < kInH) {
-        s_in[0][ri][ci] = v0;
-        s_in[1][ri][ci] = v1;
-        s_in[2][ri][ci] = v2;
+      for (int c = 0; c < 3; ++c) {
+        const float4 q = *reinterpret_cast<const float4*>(p + c * plane);
+        vals[c][0] = q.x;
+        vals[c][1] = q.y;
+        vals[c][2] = q.z;
+        vals[c][3] = q.w;
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int lxx = x0 - 4 + 4 * g + j;
+        const int gx = interior ? lxx : mirror(lxx, a.W);
+        const float* p = a.in + size_t(gy) * a.stride + gx;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) vals[c][j] = p[c * plane];
       }
     }
-    s_w[0][v][g] = w0;
-    s_w[1][v][g] = w1;
-    s_w[2][v][g] = w2;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      uint32_t w = 0;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) w |= guide_byte(vals[c][j], a.minv[c], a.scale[c]) << (8 * j);
+      s_w[c][v][g] = w;
+    }
+    const int ri = v - 1;
+    if (ri >= 0 && ri < kInH) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int ci = 4 * g + j - 1;
+        if (ci >= 0 && ci < kInW)
+#pragma unroll
+          for (int c = 0; c < 3; ++c) s_in[c][ri][ci] = vals[c][j];
+      }
+    }
   }
   if (tid < 2) s_bad[tid] = 0;
   __syncthreads();
 
-  // B: guide words at every start column; C: region scans.
-  for (int it = tid; it < 3 * kPH * (kPW - 1); it += kThreads) {
-    const int c = it / (kPH * (kPW - 1));
-    const int rem = it % (kPH * (kPW - 1));
-    const int v = rem / (kPW - 1), u = rem % (kPW - 1);
-    s_p[c][v][u] = __builtin_amdgcn_alignbyte(s_w[c][v][(u >> 2) + 1], s_w[c][v][u >> 2], u & 3);
+  // B: guide words at every start column (four per aligned word pair).
+  for (int it = tid; it < 3 * kPH * (kGW - 1); it += kThreads) {
+    const int c = it / (kPH * (kGW - 1));
+    const int rem = it - c * (kPH * (kGW - 1));
+    const int v = rem / (kGW - 1), g = rem - v * (kGW - 1);
+    const uint32_t lo = s_w[c][v][g], hi = s_w[c][v][g + 1];
+    uint32_t* dst = &s_p[c][v][4 * g];
+    dst[0] = lo;
+    dst[1] = __builtin_amdgcn_alignbyte(hi, lo, 1);
+    dst[2] = __builtin_amdgcn_alignbyte(hi, lo, 2);
+    if (4 * g + 3 < kPW - 1) dst[3] = __builtin_amdgcn_alignbyte(hi, lo, 3);
   }
   if (tid < 32) load_tile_info(a.info, a.Wb, a.Hb, gbx0, gby0, tid, s_strat, s_owner, s_bad);
   // Per-block range of `scaled` (J.2.4) over the block's pixels inside the
