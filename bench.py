@@ -1,18 +1,23 @@
 """Benchmark: decoded megapixels per second, coefficients -> RGB, on one GPU.
 
-Workload: one 2048x2048 frame, DctSelect drawn per 32x32 region from ten
-transform types, quant field U{1..32}, chroma-from-luma U[-1, 1] per 64x64
-tile, two edge-preserving filter passes, Gaborish, binary32 linear RGB out
-(synthetic inputs, seeded).  A step is one whole reconstruction of the frame
-with its inputs already resident in device memory: reconstruct, two EPF
-passes, Gaborish + XYB -> RGB.  The steps call the same stage entry points as
-jxlr_decode, with HIP events recorded between them on the launch stream, so
-that each kernel's duration is measured inside the timed region.
+Default workload (c2): one 2048x2048 frame, DctSelect drawn per 32x32 region
+from ten transform types, quant field U{1..32}, chroma-from-luma U[-1, 1] per
+64x64 tile, two edge-preserving filter passes, Gaborish, binary32 linear RGB
+out (synthetic inputs, seeded).  A step is one whole reconstruction of the
+frame with its inputs already resident in device memory: block info +
+reconstruct, two EPF passes, Gaborish + XYB -> RGB.  The steps call the same
+stage entry points as jxlr_decode, with HIP events recorded between them on
+the launch stream, so that each kernel's duration is measured inside the
+timed region.
 
-After timing, the last step's output is compared with the FP64 oracle on the
-full frame (max-abs error on [0,1]-scaled RGB outside pixels whose EPF
-integer decisions differ between binary32 and binary64), and the oracle's
-wall time for that same decode on the host cores is the CPU baseline.
+Batch workloads (--workload c4 | c1x1024): a step is one replay of the
+captured HIP graph of the whole batch (persistent stage kernels with the
+autotuned schedule); a second timed loop runs the same batch stage by stage
+with events between the stages for the per-kernel durations.
+
+After timing, the output is compared with the FP64 oracle (full frame for
+c1/c2/c3; a sample of frames for the batches), and the oracle's wall time on
+the host cores over a bounded sample is the CPU baseline.
 
 Prints one JSON line.
 """
@@ -36,41 +41,47 @@ ALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 # 3 + 2 adds of the 4x3 patch box sum, 6 ops of Weight and the threshold,
 # 4 FMAs of the weighted sums (3 channels and the weight total).
 EPF_OPS_PER_PX = 56 * (1 + 5 + 7 + 4)
-# Algorithmic HBM bytes per pixel of the other kernels (int32 AC in, f32 XYB
-# out for reconstruct; f32 XYB in, f32 RGB out for finish).
+# Algorithmic HBM bytes per pixel of the other kernels: int32 AC in, f32 XYB
+# out for reconstruct; f32 XYB in, f32 / u8 / u16 RGB out for finish.
 RECON_BYTES_PER_PX = 12 + 12
-FINISH_BYTES_PER_PX = 12 + 12
+FINISH_BYTES_PER_PX = {0: 12 + 12, 1: 12 + 3, 2: 12 + 6}
+
+METRIC = "decoded MP/s (coeffs->RGB) at stated max-abs err vs FP64; p50/p99 latency"
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=30)
-    ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3"])
-    ap.add_argument("--no-check", action="store_true", help="skip the oracle comparison")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; use --gpus 1",
-                          "n_gpus": args.gpus}))
-        sys.exit(2)
+def roofline_of(kernels, weights):
+    """kernels: name -> dict(ms, bound, achieved); weights: launches per step."""
+    dominant = max(kernels, key=lambda k: kernels[k]["ms"] * weights.get(k, 1))
+    dk = kernels[dominant]
+    if dk["bound"] == "alu":
+        return dict(bound="alu", kernel=dominant, achieved=round(dk["achieved"], 3),
+                    peak=round(ALU_PEAK_TOPS, 3), unit="Top/s",
+                    frac=round(dk["achieved"] / ALU_PEAK_TOPS, 4), avg_ms=round(dk["ms"], 5),
+                    ops_per_px=EPF_OPS_PER_PX, traffic=None)
+    return dict(bound="hbm", kernel=dominant, achieved=round(dk["achieved"], 1), peak=HBM_PEAK_GBS,
+                unit="GB/s", frac=round(dk["achieved"] / HBM_PEAK_GBS, 4),
+                avg_ms=round(dk["ms"], 5), bytes_per_px=dk.get("bytes_per_px"), traffic=None)
 
-    import numpy as np
-    import torch
-    from paper_1908_03565_amd import jxlr as J
-    from paper_1908_03565_amd import workload as wl
 
-    assert torch.cuda.is_available(), "bench.py needs a GPU"
-    torch.cuda.set_device(0)
+def kernel_table(px, recon_ms, epf_ms, fin_ms, out_format, names):
+    k = {names[0]: dict(ms=recon_ms, bound="hbm", bytes_per_px=RECON_BYTES_PER_PX,
+                        achieved=px * RECON_BYTES_PER_PX / (recon_ms / 1e3) / 1e9),
+         names[2]: dict(ms=fin_ms, bound="hbm", bytes_per_px=FINISH_BYTES_PER_PX[out_format],
+                        achieved=px * FINISH_BYTES_PER_PX[out_format] / (fin_ms / 1e3) / 1e9)}
+    if epf_ms is not None:
+        k[names[1]] = dict(ms=epf_ms, bound="alu", achieved=px * EPF_OPS_PER_PX / (epf_ms / 1e3) / 1e12)
+    return k
+
+
+def bench_frame(args, J, wl, torch, np):
     log(f"bench: generating workload {args.workload}")
     frame = getattr(wl, args.workload)()
     W, H = frame["xsize"], frame["ysize"]
-    p = J.params(W, H, **frame["params"])
+    p = J.params(W, H, out_format=frame["out_format"], **frame["params"])
     st = J.validate_maps_host(p, frame)
     assert st == 0, st
     ctx = J.Context(0)
@@ -122,26 +133,9 @@ def main():
     log(f"bench: {ms_per_step:.4f} ms/step, {value:.1f} MP/s; recon {recon_ms:.4f} ms, "
         f"epf {['%.4f' % x for x in epf_ms]} ms, finish {fin_ms:.4f} ms")
 
-    px = W * H
-    kernels = {"recon_kernel": dict(ms=recon_ms, bound="hbm",
-                                    achieved=px * RECON_BYTES_PER_PX / (recon_ms / 1e3) / 1e9),
-               "finish_kernel": dict(ms=fin_ms, bound="hbm",
-                                     achieved=px * FINISH_BYTES_PER_PX / (fin_ms / 1e3) / 1e9)}
-    if n_epf:
-        e_ms = statistics.mean(epf_ms)
-        kernels["epf_kernel"] = dict(ms=e_ms, bound="alu",
-                                     achieved=px * EPF_OPS_PER_PX / (e_ms / 1e3) / 1e12)
-    dominant = max(kernels, key=lambda k: kernels[k]["ms"] * (n_epf if k == "epf_kernel" else 1))
-    dk = kernels[dominant]
-    if dk["bound"] == "alu":
-        roofline = dict(bound="alu", kernel=dominant, achieved=round(dk["achieved"], 3),
-                        peak=round(ALU_PEAK_TOPS, 3), unit="Top/s",
-                        frac=round(dk["achieved"] / ALU_PEAK_TOPS, 4),
-                        avg_ms=round(dk["ms"], 5), ops_per_px=EPF_OPS_PER_PX, traffic=None)
-    else:
-        roofline = dict(bound="hbm", kernel=dominant, achieved=round(dk["achieved"], 1),
-                        peak=HBM_PEAK_GBS, unit="GB/s", frac=round(dk["achieved"] / HBM_PEAK_GBS, 4),
-                        avg_ms=round(dk["ms"], 5), traffic=None)
+    kernels = kernel_table(W * H, recon_ms, statistics.mean(epf_ms) if n_epf else None, fin_ms,
+                           p.out_format, ("recon_kernel", "epf_kernel", "finish_kernel"))
+    roofline = roofline_of(kernels, {"epf_kernel": n_epf})
 
     err = None
     cpu = None
@@ -156,10 +150,9 @@ def main():
         cpu = dict(value=round(mp / cpu_s, 4), unit="MP/s", cores=O.num_threads(), kind="oracle",
                    sample=f"one full {W}x{H} decode ({cpu_s:.2f} s), FP64 scalar C, OpenMP")
         if not args.no_check:
-            from tests.parity import gpu_stages, compare_rgb
-            gpu = gpu_stages(ctx, p, df)
+            gpu = P.gpu_stages(ctx, p, df)
             np.testing.assert_array_equal(gpu["out"], out.cpu().numpy())
-            cmp = compare_rgb(p, gpu, orc)
+            cmp = P.compare_rgb(p, gpu, orc)
             err = dict(max_abs_err=cmp["max_err"], tol=P.RGB_TOL,
                        flip_affected_px=cmp["affected"],
                        max_abs_err_flip_affected=cmp["max_err_affected"], passes=cmp["passes"])
@@ -168,19 +161,10 @@ def main():
         if args.no_cpu_baseline:
             cpu = None
 
-    res = {
-        "metric": "decoded MP/s (coeffs->RGB) at stated max-abs err vs FP64; p50/p99 latency",
+    return {
         "value": round(value, 2),
-        "unit": "MP/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
         "ms_per_step": round(ms_per_step, 5),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
         "dtype": "f32",
-        "data": "synthetic",
         "config": {"workload": frame["name"], "xsize": W, "ysize": H, "epf_iters": n_epf,
                    "gaborish": bool(p.gab), "output": "f32 linear RGB / 255",
                    "frames_per_step": 1},
@@ -193,6 +177,217 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
+
+
+def _batch_frames(args, wl):
+    if args.workload == "c4":
+        log("bench: generating the 64-frame batch")
+        return wl.c4(), "c4_batch64_loguniform_256_3072_epf1_u8srgb"
+    f = wl.c1()
+    return [f] * 1024, "c1x1024_256x256_dct8"
+
+
+def bench_batch(args, J, wl, torch, np):
+    from paper_1908_03565_amd import tuning
+    frames, name = _batch_frames(args, wl)
+    ctx = J.Context(0)
+    ps, dfs, outs = [], [], []
+    for i, fr in enumerate(frames):
+        p = J.params(fr["xsize"], fr["ysize"], out_format=fr["out_format"], **fr["params"])
+        if i > 0 and fr is frames[0]:
+            df = dfs[0].clone()  # repeated inputs still get their own device memory
+        else:
+            assert J.validate_maps_host(p, fr) == 0
+            df = J.DeviceFrame(fr)
+        ps.append(p)
+        dfs.append(df)
+        outs.append(ctx.empty_out(p))
+    ios = [df.io(o) for df, o in zip(dfs, outs)]
+    stream = torch.cuda.current_stream()
+    ws = ctx.batch_workspace(ps)
+    plan = ctx.batch_prepare(ps, ios, ws)
+    px = sum(p.xsize * p.ysize for p in ps)
+    mp = px / 1e6
+    log(f"bench: {len(ps)} frames, {mp:.2f} MP, {plan.total_tiles} tiles, "
+        f"workspace {ws.numel() / 2**30:.2f} GiB")
+    cfg, tinfo = tuning.tuned_config(ctx, plan, stream=stream, retune=args.retune)
+    log(f"bench: schedule {cfg.as_dict()} ({'cached' if tinfo['cached'] else 'tuned'}, "
+        f"{tinfo['tuned_ms']} ms)")
+    graph = ctx.graph(plan, cfg)
+    for _ in range(args.warmup):
+        graph.launch(stream)
+    torch.cuda.synchronize()
+    log(f"bench: warmup done ({args.warmup} graph replays); timing {args.steps}")
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for a, b in ev:
+        a.record(stream)
+        graph.launch(stream)
+        b.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    assert ctx.device_status() == 0
+    total_ms = ev[0][0].elapsed_time(ev[-1][1])
+    ms_per_step = total_ms / args.steps
+    lat = [a.elapsed_time(b) for a, b in ev]
+    value = mp / (ms_per_step / 1e3)
+    log(f"bench: {ms_per_step:.4f} ms/step (graph), {value:.1f} MP/s")
+
+    # stage-by-stage loop with events between the stages (same schedule)
+    n_epf = plan.max_epf_iters
+    reps = max(3, args.steps // 2)
+    sev = [[torch.cuda.Event(enable_timing=True) for _ in range(4 + n_epf)] for _ in range(reps)]
+    for e in sev:
+        e[0].record(stream)
+        ctx.batch_stage(plan, J.STAGE_INFO, cfg.grid_info, 0, 0, stream)
+        e[1].record(stream)
+        ctx.batch_stage(plan, J.STAGE_RECON, cfg.grid_recon, cfg.order_recon, 0, stream)
+        e[2].record(stream)
+        for k in range(n_epf):
+            ctx.batch_stage(plan, J.STAGE_EPF, cfg.grid_epf, cfg.order_epf, k, stream)
+            e[3 + k].record(stream)
+        ctx.batch_stage(plan, J.STAGE_FINISH, cfg.grid_finish, cfg.order_finish, 0, stream)
+        e[3 + n_epf].record(stream)
+    torch.cuda.synchronize()
+    stage = lambda i: statistics.mean(e[i].elapsed_time(e[i + 1]) for e in sev)
+    info_ms, recon_ms = stage(0), stage(1)
+    epf_ms = [stage(2 + k) for k in range(n_epf)]
+    fin_ms = stage(2 + n_epf)
+    eager_ms = statistics.mean(e[0].elapsed_time(e[-1]) for e in sev)
+    log(f"bench: eager stages: info {info_ms:.4f} recon {recon_ms:.4f} epf "
+        f"{['%.4f' % x for x in epf_ms]} finish {fin_ms:.4f} (sum {eager_ms:.4f} ms)")
+    fmt = ps[0].out_format
+    kernels = kernel_table(px, recon_ms, statistics.mean(epf_ms) if n_epf else None, fin_ms, fmt,
+                           ("recon_batch_kernel", "epf_batch_kernel", "finish_batch_kernel"))
+    roofline = roofline_of(kernels, {"epf_batch_kernel": n_epf})
+
+    # every frame of the batch equals its single-frame decode; a sample of
+    # frames against the oracle
+    err, cpu = None, None
+    if not args.no_check or not args.no_cpu_baseline:
+        from oracle import oracle as O
+        from tests import parity as P
+        order = sorted(range(len(ps)), key=lambda i: ps[i].xsize * ps[i].ysize)
+        uniq = order if args.workload == "c4" else [0]
+        if not args.no_check:
+            log("bench: batch vs single-frame decode, every frame")
+            for i in range(len(ps)):
+                o = ctx.empty_out(ps[i])
+                ctx.decode(ps[i], dfs[i], o, ctx.workspace(ps[i]), stream=stream)
+                assert torch.equal(o, outs[i]), f"frame {i} differs from its single-frame decode"
+            torch.cuda.synchronize()
+            sample = uniq[:3]
+            res = []
+            for i in sample:
+                fr, p = frames[i], ps[i]
+                q = O.params(fr["xsize"], fr["ysize"], **fr["params"])
+                orc = O.decode_stages(q, fr)
+                gpu = P.gpu_stages(ctx, p, dfs[i])
+                assert np.array_equal(gpu["out"], outs[i].cpu().numpy())
+                if p.out_format == 0:
+                    cmp = P.compare_rgb(p, gpu, orc)
+                    res.append(dict(frame=i, size=[p.xsize, p.ysize], max_abs_err=cmp["max_err"],
+                                    flip_affected_px=cmp["affected"]))
+                else:
+                    # codes = the oracle's rounding of the exported linear
+                    # values, on every sample; against the all-binary64
+                    # oracle, equal wherever the value is not within the
+                    # binary32 error of a code boundary
+                    bits = 8 if p.out_format == 1 else 16
+                    p32 = J.params(p.xsize, p.ysize, out_format=0, **fr["params"])
+                    lin = ctx.empty_out(p32)
+                    ctx.decode(p32, dfs[i], lin, ctx.workspace(p32), stream=stream)
+                    ref = O.quantize_srgb(bits, lin.cpu().numpy().astype(np.float64))
+                    exact = bool(np.array_equal(ref, gpu["out"]))
+                    assert exact, f"frame {i}: codes differ from the rounding of the same values"
+                    eq, firm, maxd = P.srgb_codes_check(p, gpu["out"], orc, gpu["epf"], bits)
+                    res.append(dict(frame=i, size=[p.xsize, p.ysize], codes_equal_rounding=exact,
+                                    firm_codes_equal=eq, firm_codes=firm, max_code_diff=maxd))
+            err = dict(batch_equals_single_frame=True, oracle_sample=res)
+            log(f"bench: oracle sample {res}")
+        if not args.no_cpu_baseline:
+            # the batch's distinct frames, smallest first, cycled until the
+            # time bound (the whole batch when it ends sooner)
+            done_px, t = 0, time.perf_counter()
+            n_done = 0
+            while True:
+                fr = frames[uniq[n_done % len(uniq)]]
+                O.decode(O.params(fr["xsize"], fr["ysize"], **fr["params"]), fr)
+                done_px += fr["xsize"] * fr["ysize"]
+                n_done += 1
+                if time.perf_counter() - t > args.cpu_seconds or n_done == len(ps):
+                    break
+            cpu_s = time.perf_counter() - t
+            cpu = dict(value=round(done_px / 1e6 / cpu_s, 4), unit="MP/s", cores=O.num_threads(),
+                       kind="oracle",
+                       sample=f"{n_done} frame(s) of the batch, smallest first, {done_px / 1e6:.2f} MP "
+                              f"in {cpu_s:.2f} s, FP64 scalar C, OpenMP")
+
+    out_name = {0: "f32 linear RGB / 255", 1: "u8 sRGB", 2: "u16 sRGB"}[fmt]
+    return {
+        "value": round(value, 2),
+        "ms_per_step": round(ms_per_step, 5),
+        "dtype": "f32",
+        "config": {"workload": name, "frames_per_step": len(ps), "megapixels_per_step": round(mp, 4),
+                   "tiles": plan.total_tiles, "epf_iters": n_epf, "output": out_name,
+                   "schedule": cfg.as_dict(), "hip_graph": True},
+        "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 5),
+                       "p99": round(float(np.percentile(lat, 99)), 5)},
+        "stage_ms": {"info": round(info_ms, 5), "reconstruct": round(recon_ms, 5),
+                     "epf": [round(x, 5) for x in epf_ms], "finish": round(fin_ms, 5),
+                     "eager_sum": round(eager_ms, 5)},
+        "host_wall_ms_per_step": round(wall / args.steps * 1e3, 5),
+        "error": err,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c1x1024"])
+    ap.add_argument("--no-check", action="store_true", help="skip the oracle comparison")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0,
+                    help="bound on the oracle's CPU time for the batch workloads")
+    ap.add_argument("--retune", action="store_true", help="ignore cached batch schedules")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB a few times (the reference "
+                         "kernel that scales the HBM byte counters) and exit")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this implementation runs on one GPU only; use --gpus 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_1908_03565_amd import jxlr as J
+    from paper_1908_03565_amd import workload as wl
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    if args.copy_probe:
+        n = args.copy_probe * 2**20 // 4
+        src = torch.rand(n, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read": n * 4, "copy_probe_bytes_written": n * 4,
+                          "launches": 5}))
+        return
+    run = bench_batch if args.workload in ("c4", "c1x1024") else bench_frame
+    r = run(args, J, wl, torch, np)
+    res = {"metric": METRIC, "value": r.pop("value"), "unit": "MP/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": r.pop("ms_per_step"),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": r.pop("dtype"), "data": "synthetic"}
+    res.update(r)
     print(json.dumps(res))
 
 

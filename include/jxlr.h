@@ -199,6 +199,97 @@ jxlr_status jxlr_epf_pass(jxlr_ctx* ctx, const jxlr_frame_params* p, const jxlr_
 jxlr_status jxlr_finish(jxlr_ctx* ctx, const jxlr_frame_params* p, const jxlr_frame_io* io,
                         const float* xyb, size_t xyb_stride, hipStream_t stream);
 
+/* ---- batches of frames ------------------------------------------------------
+ * A batch decodes n independent frames (each with its own sizes, parameters
+ * and inputs) in one launch per stage: the tiles of all frames form one list
+ * that persistent workgroups walk, so small frames share the GPU instead of
+ * each leaving most of it idle.  Results are bit-identical to jxlr_decode of
+ * each frame alone. */
+
+/* Device workspace for a batch: a descriptor header plus, per frame, what
+ * jxlr_workspace_bytes(&p[i]) names; 0 if n <= 0 or a parameter set is out of
+ * range. */
+size_t jxlr_batch_workspace_bytes(int n, const jxlr_frame_params* p);
+
+/* Filled by jxlr_batch_prepare; describes a batch written into `ws`. */
+typedef struct jxlr_batch_plan {
+  void* ws;
+  size_t ws_bytes;
+  int n;
+  int total_tiles;   /* 64x32 pixel tiles over all frames */
+  int total_regions; /* 32x32 DctSelect regions over all frames */
+  int max_epf_iters;
+  size_t frames_offset, tile_start_offset, region_start_offset;
+} jxlr_batch_plan;
+
+/* Schedule of the four persistent stage kernels.  grid_*: workgroup count;
+ * 0 picks one workgroup per tile (per 256 regions for the block-info stage)
+ * and larger values are clamped down to that.  order_*: 0 strided (tile t to
+ * workgroup t mod grid); 1 XCD-contiguous (each of the eight XCDs takes one
+ * contiguous eighth of the tile list, so neighbouring tiles share an L2;
+ * the grid is rounded down to a multiple of 8, and below 8 order 0 is used).
+ * The output does not depend on the schedule. */
+typedef struct jxlr_launch_config {
+  int grid_info;
+  int grid_recon;
+  int grid_epf;
+  int grid_finish;
+  int order_recon;
+  int order_epf;
+  int order_finish;
+} jxlr_launch_config;
+
+/* Stages of a batch, for jxlr_batch_stage. */
+enum { JXLR_STAGE_INFO = 0, JXLR_STAGE_RECON = 1, JXLR_STAGE_EPF = 2, JXLR_STAGE_FINISH = 3 };
+
+/* Validates every frame as the single-frame entry points do and writes the
+ * batch descriptors into `ws` (device memory, ws_bytes >=
+ * jxlr_batch_workspace_bytes(n, p)) with a synchronous copy.  p[i] and io[i]
+ * are host arrays of n entries; the device buffers io[i] names must stay
+ * valid while the plan is run.  Calls no kernel. */
+jxlr_status jxlr_batch_prepare(jxlr_ctx* ctx, int n, const jxlr_frame_params* p,
+                               const jxlr_frame_io* io, void* ws, size_t ws_bytes,
+                               jxlr_batch_plan* plan);
+
+/* Enqueues the whole path for every frame of the plan on `stream`: block
+ * info, reconstruction, max_epf_iters EPF passes (a frame with fewer passes
+ * sits out the rest) and finish.  cfg may be NULL. */
+jxlr_status jxlr_batch_run(jxlr_ctx* ctx, const jxlr_batch_plan* plan,
+                           const jxlr_launch_config* cfg, hipStream_t stream);
+
+/* Enqueues one stage of a prepared batch (EPF: pass epf_pass, reading and
+ * writing the XYB buffer pair that pass uses).  Each stage reads what the
+ * stage before it wrote, so stages must run in jxlr_batch_run's order for a
+ * correct result; repeating one stage alone is idempotent. */
+jxlr_status jxlr_batch_stage(jxlr_ctx* ctx, const jxlr_batch_plan* plan, int stage, int grid,
+                             int order, int epf_pass, hipStream_t stream);
+
+/* Autotuner: picks, per tile stage, the workgroup count and tile order with
+ * the shortest time on this device for this batch.  Candidates: one
+ * workgroup per tile, and persistent grids of 1-4 times (compute units x
+ * resident workgroups per compute unit) in both orders; each timed with HIP
+ * events as the best of three groups of `reps` launches.  Runs the batch
+ * before and after (its outputs are written as by jxlr_batch_run) and
+ * synchronizes `stream`.  best_ms (may be NULL) receives the tuned stage time
+ * sum of one run, EPF counted max_epf_iters times. */
+jxlr_status jxlr_autotune(jxlr_ctx* ctx, const jxlr_batch_plan* plan, int reps,
+                          jxlr_launch_config* best, float* best_ms, hipStream_t stream);
+
+/* jxlr_batch_prepare followed by jxlr_batch_run with the default config. */
+jxlr_status jxlr_decode_batch(jxlr_ctx* ctx, int n, const jxlr_frame_params* p,
+                              const jxlr_frame_io* io, void* ws, size_t ws_bytes,
+                              hipStream_t stream);
+
+/* A prepared batch captured once into a HIP graph, for callers that replay the
+ * same batch shape (the plan's buffers are fixed; refill their contents
+ * between launches).  The capture uses a private default-priority stream and
+ * records kernel nodes only. */
+typedef struct jxlr_graph jxlr_graph;
+jxlr_status jxlr_graph_create(jxlr_ctx* ctx, const jxlr_batch_plan* plan,
+                              const jxlr_launch_config* cfg, jxlr_graph** out);
+jxlr_status jxlr_graph_launch(jxlr_graph* g, hipStream_t stream);
+void jxlr_graph_destroy(jxlr_graph* g);
+
 /* Reads and clears the sticky device-validation flag: JXLR_OK or
  * JXLR_E_DEVICE_VALIDATION.  Synchronizes `stream`. */
 jxlr_status jxlr_get_device_status(jxlr_ctx* ctx, hipStream_t stream);

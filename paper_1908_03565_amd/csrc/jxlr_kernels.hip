@@ -87,9 +87,8 @@ struct InfoArgs {
 // disjoint from earlier ones.  Regions start at multiples of 4 blocks and
 // varblocks are at most 4x4 blocks, so a region is scanned on its own.
 // Coverage is a 16-bit mask in registers.
-__global__ __launch_bounds__(kThreads) void blockinfo_kernel(InfoArgs a) {
+__device__ inline void blockinfo_region(const InfoArgs& a, int rid) {
   const int Rw = (a.Wb + 3) / 4, Rh = (a.Hb + 3) / 4;
-  const int rid = blockIdx.x * kThreads + threadIdx.x;
   if (rid >= Rw * Rh) return;
   const int gbx0 = 4 * (rid % Rw), gby0 = 4 * (rid / Rw);
   const int nbx = min(4, a.Wb - gbx0), nby = min(4, a.Hb - gby0);
@@ -318,7 +317,8 @@ __device__ inline int dq_off_lut(int s) {
   return int(v & 0xFFu) * 192;
 }
 
-__global__ __launch_bounds__(kRecThreads) void recon_kernel(ReconArgs a) {
+// One 64x32 tile (tile column tbx, row tby) of the reconstruction.
+__device__ inline void recon_tile(const ReconArgs& a, int tbx, int tby) {
   __shared__ float coef[3][kRecTH][kRecLd];
   // DC samples per tile block (b = row * 8 + column), zero-padded so that a
   // fixed 4x4 window starting at any block stays inside the array.
@@ -331,7 +331,7 @@ __global__ __launch_bounds__(kRecThreads) void recon_kernel(ReconArgs a) {
 
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
-  const int x0 = kRecTW * blockIdx.x, y0 = kRecTH * blockIdx.y;
+  const int x0 = kRecTW * tbx, y0 = kRecTH * tby;
   const int gbx0 = x0 / 8, gby0 = y0 / 8;
   const DeviceTables* __restrict__ T = a.tab;
 
@@ -574,7 +574,9 @@ __device__ inline uint32_t guide_byte(float v, float minv, float scale) {
   return uint32_t(floorf(g));
 }
 
-__global__ __launch_bounds__(kThreads, 2) void epf_kernel(EpfArgs a) {
+// One 64x32 output tile of an EPF pass.  Threads may return after the last
+// barrier.
+__device__ inline void epf_tile(const EpfArgs& a, int tbx, int tby) {
   __shared__ float s_in[3][kInH][kInW];
   __shared__ uint32_t s_p[3][kPH][kPW];
   __shared__ uint32_t s_w[3][kPH][kGW + 1];
@@ -584,7 +586,7 @@ __global__ __launch_bounds__(kThreads, 2) void epf_kernel(EpfArgs a) {
   __shared__ int s_bad[2];
 
   const int tid = threadIdx.x;
-  const int x0 = kEpfTW * blockIdx.x, y0 = kEpfTH * blockIdx.y;
+  const int x0 = kEpfTW * tbx, y0 = kEpfTH * tby;
   const int gbx0 = x0 / 8, gby0 = y0 / 8;
   const size_t plane = size_t(a.H) * a.stride;
 
@@ -789,6 +791,7 @@ struct FinishArgs {
   int format;
   void* out[3];
   size_t out_stride;
+  const float* thr;  // decision thresholds of the 8- or 16-bit code
 };
 
 __device__ inline float srgb_encode(float v) {
@@ -796,10 +799,19 @@ __device__ inline float srgb_encode(float v) {
   return v <= 0.0031308f ? 12.92f * v : 1.055f * powf(v, 1.0f / 2.4f) - 0.055f;
 }
 
-__global__ __launch_bounds__(kThreads) void finish_kernel(FinishArgs a) {
-  const int x = blockIdx.x * 64 + (threadIdx.x & 63);
-  const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
-  if (x >= a.W || y >= a.H) return;
+// Output code of a linear sample, identical to the binary64 definition
+// (sRGB transfer of the clamped value, round half up): the binary32 estimate
+// is within one code of it, and the thresholds (the smallest binary32 value
+// of each code, computed in binary64 on the host) settle the last step.
+__device__ inline int srgb_code(float v, const float* __restrict__ thr, int maxv) {
+  int c = int(floorf(srgb_encode(v) * float(maxv) + 0.5f));
+  c = min(max(c, 0), maxv);
+  c += v >= thr[c + 1] ? 1 : 0;
+  c -= v < thr[c] ? 1 : 0;
+  return c;
+}
+
+__device__ inline void finish_pixel(const FinishArgs& a, int x, int y) {
   const size_t plane = size_t(a.H) * a.stride;
   float v[3];
   if (a.gab) {
@@ -828,12 +840,140 @@ __global__ __launch_bounds__(kThreads) void finish_kernel(FinishArgs a) {
   if (a.format == JXLR_OUT_F32) {
     for (int c = 0; c < 3; ++c) static_cast<float*>(a.out[c])[o] = rgb[c];
   } else if (a.format == JXLR_OUT_U8_SRGB) {
-    for (int c = 0; c < 3; ++c)
-      static_cast<uint8_t*>(a.out[c])[o] = uint8_t(floorf(srgb_encode(rgb[c]) * 255.0f + 0.5f));
+    for (int c = 0; c < 3; ++c) static_cast<uint8_t*>(a.out[c])[o] = uint8_t(srgb_code(rgb[c], a.thr, 255));
   } else {
     for (int c = 0; c < 3; ++c)
-      static_cast<uint16_t*>(a.out[c])[o] =
-          uint16_t(floorf(srgb_encode(rgb[c]) * 65535.0f + 0.5f));
+      static_cast<uint16_t*>(a.out[c])[o] = uint16_t(srgb_code(rgb[c], a.thr, 65535));
+  }
+}
+
+// One 64x32 tile: thread = column, rows threadIdx.x / 64 + 4 k.
+__device__ inline void finish_tile(const FinishArgs& a, int tbx, int tby) {
+  const int x = 64 * tbx + (threadIdx.x & 63);
+  if (x >= a.W) return;
+  for (int k = 0; k < 8; ++k) {
+    const int y = 32 * tby + (threadIdx.x >> 6) + 4 * k;
+    if (y >= a.H) break;
+    finish_pixel(a, x, y);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Kernels.  Single-frame kernels take the frame's arguments by value and map
+// workgroups to tiles directly.  Batch kernels walk a table of the 64x32
+// tiles (and 32x32 regions) of all frames of a batch with a grid-stride
+// loop, so a fixed, tunable grid serves any batch; the frame of a tile is
+// found by binary search over per-frame tile offsets.
+
+__global__ __launch_bounds__(kThreads) void blockinfo_kernel(InfoArgs a) {
+  blockinfo_region(a, blockIdx.x * kThreads + threadIdx.x);
+}
+__global__ __launch_bounds__(kRecThreads) void recon_kernel(ReconArgs a) {
+  recon_tile(a, blockIdx.x, blockIdx.y);
+}
+__global__ __launch_bounds__(kThreads, 2) void epf_kernel(EpfArgs a) {
+  epf_tile(a, blockIdx.x, blockIdx.y);
+}
+__global__ __launch_bounds__(kThreads) void finish_kernel(FinishArgs a) {
+  finish_tile(a, blockIdx.x, blockIdx.y);
+}
+
+// The batch kernels share one tile list over reconstruction, EPF and finish.
+static_assert(kRecTW == kEpfTW && kRecTH == kEpfTH && kRecTW == 64 && kRecTH == 32,
+              "stage tiles must coincide");
+
+// Everything the batch kernels need about one frame of a batch.
+struct FrameDesc {
+  InfoArgs info;
+  ReconArgs rec;
+  EpfArgs epf;     // in/out are set per pass
+  FinishArgs fin;  // in is set from the number of EPF passes
+  float* xyb[2];
+  int epf_iters;
+  int tiles_x;     // 64x32 tiles per row
+};
+
+struct BatchArgs {
+  const FrameDesc* __restrict__ frames;
+  const int* __restrict__ tile_start;    // n + 1 prefix offsets of 64x32 tiles
+  const int* __restrict__ region_start;  // n + 1 prefix offsets of 32x32 regions
+  int n;
+  int pass;   // EPF pass of epf_batch_kernel
+  int order;  // tile order of the tile kernels, see TileRange
+};
+
+__device__ inline int find_frame(const int* __restrict__ start, int n, int t) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (start[mid] <= t) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// The tiles a persistent workgroup visits.  Order 0: strided, tile t goes to
+// workgroup t mod gridDim.x.  Order 1 (gridDim.x a multiple of 8): workgroups
+// are handed to the eight XCDs round-robin, so workgroup b runs on XCD b mod 8;
+// it takes a contiguous run of the tile list such that each XCD covers one
+// contiguous eighth of it, and tiles that share filter halos share an L2.
+struct TileRange {
+  int t, end, step;
+  __device__ TileRange(int order, int total) {
+    if (order == 1) {
+      const int m = gridDim.x >> 3;
+      const int l = (blockIdx.x & 7) * m + (blockIdx.x >> 3);
+      t = int((long long)l * total / gridDim.x);
+      end = int((long long)(l + 1) * total / gridDim.x);
+      step = 1;
+    } else {
+      t = blockIdx.x;
+      end = total;
+      step = gridDim.x;
+    }
+  }
+};
+
+__global__ __launch_bounds__(kThreads) void blockinfo_batch_kernel(BatchArgs b) {
+  const int total = b.region_start[b.n];
+  for (int rid = blockIdx.x * kThreads + threadIdx.x; rid < total; rid += gridDim.x * kThreads) {
+    const int f = find_frame(b.region_start, b.n, rid);
+    blockinfo_region(b.frames[f].info, rid - b.region_start[f]);
+  }
+}
+
+__global__ __launch_bounds__(kRecThreads) void recon_batch_kernel(BatchArgs b) {
+  for (TileRange r(b.order, b.tile_start[b.n]); r.t < r.end; r.t += r.step) {
+    __syncthreads();
+    const int f = find_frame(b.tile_start, b.n, r.t);
+    const FrameDesc& d = b.frames[f];
+    const int lt = r.t - b.tile_start[f];
+    recon_tile(d.rec, lt % d.tiles_x, lt / d.tiles_x);
+  }
+}
+
+__global__ __launch_bounds__(kThreads, 2) void epf_batch_kernel(BatchArgs b) {
+  for (TileRange r(b.order, b.tile_start[b.n]); r.t < r.end; r.t += r.step) {
+    __syncthreads();
+    const int f = find_frame(b.tile_start, b.n, r.t);
+    const FrameDesc& d = b.frames[f];
+    if (b.pass >= d.epf_iters) continue;  // uniform over the workgroup
+    EpfArgs a = d.epf;
+    a.in = d.xyb[b.pass & 1];
+    a.out = d.xyb[(b.pass + 1) & 1];
+    const int lt = r.t - b.tile_start[f];
+    epf_tile(a, lt % d.tiles_x, lt / d.tiles_x);
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void finish_batch_kernel(BatchArgs b) {
+  for (TileRange r(b.order, b.tile_start[b.n]); r.t < r.end; r.t += r.step) {
+    const int f = find_frame(b.tile_start, b.n, r.t);
+    const FrameDesc& d = b.frames[f];
+    FinishArgs a = d.fin;
+    a.in = d.xyb[d.epf_iters & 1];
+    const int lt = r.t - b.tile_start[f];
+    finish_tile(a, lt % d.tiles_x, lt / d.tiles_x);
   }
 }
 
@@ -1013,25 +1153,25 @@ size_t jxlr_workspace_bytes(const jxlr_frame_params* p) {
   return info_bytes(p) + (p->epf_iters > 0 ? 2 : 1) * xyb_bytes(p);
 }
 
-jxlr_status jxlr_block_info(jxlr_ctx* ctx, const jxlr_frame_params* p, const jxlr_frame_io* io,
-                            uint8_t* info, hipStream_t stream) {
+}  // extern "C"
+
+namespace {
+
+// ---- argument builders shared by the single-frame and batch paths --------
+
+jxlr_status make_info_args(jxlr_ctx* ctx, const jxlr_frame_params* p, const jxlr_frame_io* io,
+                           uint8_t* info, InfoArgs* a) {
   if (!ctx || !info || !io || !io->strategy) return JXLR_E_NULL;
   jxlr_status st = check_params(p);
   if (st) return st;
   const int Wb = blocks_of(p->xsize), Hb = blocks_of(p->ysize);
   if (io->map_stride < size_t(Wb)) return JXLR_E_SIZE;
-  InfoArgs a{Wb, Hb, io->strategy, io->map_stride, info, ctx->status};
-  DeviceGuard g(ctx->device);
-  if (!g.ok) return JXLR_E_HIP;
-  const int regions = ((Wb + 3) / 4) * ((Hb + 3) / 4);
-  hipLaunchKernelGGL(blockinfo_kernel, dim3((regions + kThreads - 1) / kThreads), dim3(kThreads), 0,
-                     stream, a);
-  return launch_status(hipGetLastError());
+  *a = InfoArgs{Wb, Hb, io->strategy, io->map_stride, info, ctx->status};
+  return JXLR_OK;
 }
 
-jxlr_status jxlr_reconstruct(jxlr_ctx* ctx, const jxlr_frame_params* p, const jxlr_frame_io* io,
-                             const uint8_t* info, float* xyb, size_t xyb_stride,
-                             hipStream_t stream) {
+jxlr_status make_recon_args(jxlr_ctx* ctx, const jxlr_frame_params* p, const jxlr_frame_io* io,
+                            const uint8_t* info, float* xyb, size_t xyb_stride, ReconArgs* out) {
   if (!ctx || !xyb || !info) return JXLR_E_NULL;
   jxlr_status st = check_params(p);
   if (st) return st;
@@ -1064,23 +1204,21 @@ jxlr_status jxlr_reconstruct(jxlr_ctx* ctx, const jxlr_frame_params* p, const jx
   a.kx_dc = p->kx_dc;
   a.kb_dc = p->kb_dc;
   a.gscale = float(p->global_scale);
+  // F.3 kOneBias per channel
   const double kOneBias[3] = {0.05465007330715401, 0.07005449891748593, 0.049935103337343655};
   for (int c = 0; c < 3; ++c) a.one_bias[c] = float(1.0 - kOneBias[c]);
   a.xyb = xyb;
   a.xyb_stride = xyb_stride;
   a.status = ctx->status;
   a.tab = ctx->tables;
-  DeviceGuard g(ctx->device);
-  if (!g.ok) return JXLR_E_HIP;
-  dim3 grid((p->xsize + kRecTW - 1) / kRecTW, (p->ysize + kRecTH - 1) / kRecTH);
-  hipLaunchKernelGGL(recon_kernel, grid, dim3(kRecThreads), 0, stream, a);
-  return launch_status(hipGetLastError());
+  *out = a;
+  return JXLR_OK;
 }
 
-jxlr_status jxlr_epf_pass(jxlr_ctx* ctx, const jxlr_frame_params* p, const jxlr_frame_io* io,
+jxlr_status make_epf_args(jxlr_ctx* ctx, const jxlr_frame_params* p, const jxlr_frame_io* io,
                           const uint8_t* info, const float* in, float* out, size_t stride,
-                          uint8_t* guide_dbg, int32_t* sigma_dbg, hipStream_t stream) {
-  if (!ctx || !in || !out || !info) return JXLR_E_NULL;
+                          uint8_t* guide_dbg, int32_t* sigma_dbg, EpfArgs* res) {
+  if (!ctx || !info) return JXLR_E_NULL;
   jxlr_status st = check_params(p);
   if (st) return st;
   if ((st = check_maps_io(p, io, true))) return st;
@@ -1120,16 +1258,13 @@ jxlr_status jxlr_epf_pass(jxlr_ctx* ctx, const jxlr_frame_params* p, const jxlr_
   a.guide_dbg = guide_dbg;
   a.sigma_dbg = sigma_dbg;
   a.status = ctx->status;
-  DeviceGuard g(ctx->device);
-  if (!g.ok) return JXLR_E_HIP;
-  dim3 grid((p->xsize + kEpfTW - 1) / kEpfTW, (p->ysize + kEpfTH - 1) / kEpfTH);
-  hipLaunchKernelGGL(epf_kernel, grid, dim3(kThreads), 0, stream, a);
-  return launch_status(hipGetLastError());
+  *res = a;
+  return JXLR_OK;
 }
 
-jxlr_status jxlr_finish(jxlr_ctx* ctx, const jxlr_frame_params* p, const jxlr_frame_io* io,
-                        const float* xyb, size_t stride, hipStream_t stream) {
-  if (!ctx || !xyb || !io) return JXLR_E_NULL;
+jxlr_status make_finish_args(jxlr_ctx* ctx, const jxlr_frame_params* p, const jxlr_frame_io* io,
+                             const float* xyb, size_t stride, FinishArgs* res) {
+  if (!ctx || !io) return JXLR_E_NULL;
   jxlr_status st = check_params(p);
   if (st) return st;
   for (int c = 0; c < 3; ++c)
@@ -1156,10 +1291,69 @@ jxlr_status jxlr_finish(jxlr_ctx* ctx, const jxlr_frame_params* p, const jxlr_fr
   a.format = p->out_format;
   for (int c = 0; c < 3; ++c) a.out[c] = io->out[c];
   a.out_stride = io->out_stride;
+  a.thr = p->out_format == JXLR_OUT_U16_SRGB ? ctx->tables->srgb_thr16 : ctx->tables->srgb_thr8;
+  *res = a;
+  return JXLR_OK;
+}
+
+int tiles_x(const jxlr_frame_params* p) { return int((p->xsize + kRecTW - 1) / kRecTW); }
+int tiles_y(const jxlr_frame_params* p) { return int((p->ysize + kRecTH - 1) / kRecTH); }
+int regions_of(const jxlr_frame_params* p) {
+  return ((blocks_of(p->xsize) + 3) / 4) * ((blocks_of(p->ysize) + 3) / 4);
+}
+
+}  // namespace
+
+extern "C" {
+
+jxlr_status jxlr_block_info(jxlr_ctx* ctx, const jxlr_frame_params* p, const jxlr_frame_io* io,
+                            uint8_t* info, hipStream_t stream) {
+  InfoArgs a;
+  jxlr_status st = make_info_args(ctx, p, io, info, &a);
+  if (st) return st;
   DeviceGuard g(ctx->device);
   if (!g.ok) return JXLR_E_HIP;
-  dim3 grid((p->xsize + 63) / 64, (p->ysize + 3) / 4);
-  hipLaunchKernelGGL(finish_kernel, grid, dim3(kThreads), 0, stream, a);
+  const int regions = regions_of(p);
+  hipLaunchKernelGGL(blockinfo_kernel, dim3((regions + kThreads - 1) / kThreads), dim3(kThreads), 0,
+                     stream, a);
+  return launch_status(hipGetLastError());
+}
+
+jxlr_status jxlr_reconstruct(jxlr_ctx* ctx, const jxlr_frame_params* p, const jxlr_frame_io* io,
+                             const uint8_t* info, float* xyb, size_t xyb_stride,
+                             hipStream_t stream) {
+  ReconArgs a;
+  jxlr_status st = make_recon_args(ctx, p, io, info, xyb, xyb_stride, &a);
+  if (st) return st;
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return JXLR_E_HIP;
+  hipLaunchKernelGGL(recon_kernel, dim3(tiles_x(p), tiles_y(p)), dim3(kRecThreads), 0, stream, a);
+  return launch_status(hipGetLastError());
+}
+
+jxlr_status jxlr_epf_pass(jxlr_ctx* ctx, const jxlr_frame_params* p, const jxlr_frame_io* io,
+                          const uint8_t* info, const float* in, float* out, size_t stride,
+                          uint8_t* guide_dbg, int32_t* sigma_dbg, hipStream_t stream) {
+  if (!in || !out) return JXLR_E_NULL;
+  EpfArgs a;
+  jxlr_status st = make_epf_args(ctx, p, io, info, in, out, stride, guide_dbg, sigma_dbg, &a);
+  if (st) return st;
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return JXLR_E_HIP;
+  dim3 grid((p->xsize + kEpfTW - 1) / kEpfTW, (p->ysize + kEpfTH - 1) / kEpfTH);
+  hipLaunchKernelGGL(epf_kernel, grid, dim3(kThreads), 0, stream, a);
+  return launch_status(hipGetLastError());
+}
+
+jxlr_status jxlr_finish(jxlr_ctx* ctx, const jxlr_frame_params* p, const jxlr_frame_io* io,
+                        const float* xyb, size_t stride, hipStream_t stream) {
+  if (!xyb) return JXLR_E_NULL;
+  FinishArgs a;
+  jxlr_status st = make_finish_args(ctx, p, io, xyb, stride, &a);
+  if (st) return st;
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return JXLR_E_HIP;
+  hipLaunchKernelGGL(finish_kernel, dim3(tiles_x(p), tiles_y(p)), dim3(kThreads), 0, stream, a);
   return launch_status(hipGetLastError());
 }
 
@@ -1183,6 +1377,320 @@ jxlr_status jxlr_decode(jxlr_ctx* ctx, const jxlr_frame_params* p, const jxlr_fr
     std::swap(bufa, bufb);
   }
   return jxlr_finish(ctx, p, io, bufa, stride, stream);
+}
+
+}  // extern "C"
+
+// ---- batches ---------------------------------------------------------------
+
+namespace {
+struct BatchLayout {
+  size_t frames, tile_start, region_start, header, total;
+  std::vector<size_t> frame_off;  // per frame: info, then XYB buffers
+};
+
+BatchLayout batch_layout(int n, const jxlr_frame_params* p) {
+  BatchLayout L;
+  L.frames = 0;
+  L.tile_start = round256(sizeof(FrameDesc) * size_t(n));
+  L.region_start = L.tile_start + round256(sizeof(int) * size_t(n + 1));
+  L.header = L.region_start + round256(sizeof(int) * size_t(n + 1));
+  size_t off = L.header;
+  for (int i = 0; i < n; ++i) {
+    L.frame_off.push_back(off);
+    off += info_bytes(&p[i]) + (p[i].epf_iters > 0 ? 2 : 1) * xyb_bytes(&p[i]);
+  }
+  L.total = off;
+  return L;
+}
+
+jxlr_status check_plan(jxlr_ctx* ctx, const jxlr_batch_plan* plan) {
+  if (!ctx || !plan || !plan->ws) return JXLR_E_NULL;
+  if (plan->n <= 0 || plan->total_tiles <= 0 || plan->total_regions <= 0 ||
+      plan->max_epf_iters < 0 || plan->max_epf_iters > 3)
+    return JXLR_E_SIZE;
+  return JXLR_OK;
+}
+
+// Enqueues one stage of a prepared batch.  grid <= 0 picks one workgroup per
+// tile (per kThreads regions for the block-info stage); larger grids are
+// clamped to that.  Order 1 needs a multiple of 8 workgroups and falls back
+// to order 0 below 8.
+jxlr_status launch_stage(jxlr_ctx* ctx, const jxlr_batch_plan* plan, int stage, int grid,
+                         int order, int epf_pass, hipStream_t stream) {
+  char* base = static_cast<char*>(plan->ws);
+  BatchArgs b;
+  b.frames = reinterpret_cast<const FrameDesc*>(base + plan->frames_offset);
+  b.tile_start = reinterpret_cast<const int*>(base + plan->tile_start_offset);
+  b.region_start = reinterpret_cast<const int*>(base + plan->region_start_offset);
+  b.n = plan->n;
+  b.pass = epf_pass;
+  const int full = stage == JXLR_STAGE_INFO ? (plan->total_regions + kThreads - 1) / kThreads
+                                            : plan->total_tiles;
+  int gsz = grid > 0 ? std::min(grid, full) : full;
+  b.order = order == 1 && gsz >= 8 ? 1 : 0;
+  if (b.order) gsz &= ~7;
+  (void)ctx;
+  switch (stage) {
+    case JXLR_STAGE_INFO:
+      hipLaunchKernelGGL(blockinfo_batch_kernel, dim3(gsz), dim3(kThreads), 0, stream, b);
+      break;
+    case JXLR_STAGE_RECON:
+      hipLaunchKernelGGL(recon_batch_kernel, dim3(gsz), dim3(kRecThreads), 0, stream, b);
+      break;
+    case JXLR_STAGE_EPF:
+      hipLaunchKernelGGL(epf_batch_kernel, dim3(gsz), dim3(kThreads), 0, stream, b);
+      break;
+    case JXLR_STAGE_FINISH:
+      hipLaunchKernelGGL(finish_batch_kernel, dim3(gsz), dim3(kThreads), 0, stream, b);
+      break;
+    default:
+      return JXLR_E_PARAM;
+  }
+  return launch_status(hipGetLastError());
+}
+}  // namespace
+
+extern "C" {
+
+size_t jxlr_batch_workspace_bytes(int n, const jxlr_frame_params* p) {
+  if (n <= 0 || !p) return 0;
+  for (int i = 0; i < n; ++i)
+    if (check_params(&p[i]) != JXLR_OK) return 0;
+  return batch_layout(n, p).total;
+}
+
+jxlr_status jxlr_batch_prepare(jxlr_ctx* ctx, int n, const jxlr_frame_params* p,
+                               const jxlr_frame_io* io, void* ws, size_t ws_bytes,
+                               jxlr_batch_plan* plan) {
+  if (!ctx || !p || !io || !ws || !plan) return JXLR_E_NULL;
+  if (n <= 0) return JXLR_E_SIZE;
+  for (int i = 0; i < n; ++i) {
+    jxlr_status st = check_params(&p[i]);
+    if (st) return st;
+  }
+  const BatchLayout L = batch_layout(n, p);
+  if (ws_bytes < L.total) return JXLR_E_WORKSPACE;
+  char* base = static_cast<char*>(ws);
+  std::vector<FrameDesc> frames(n);
+  std::vector<int> tstart(n + 1, 0), rstart(n + 1, 0);
+  int max_epf = 0;
+  for (int i = 0; i < n; ++i) {
+    FrameDesc& d = frames[i];
+    char* fb = base + L.frame_off[i];
+    uint8_t* info = reinterpret_cast<uint8_t*>(fb);
+    d.xyb[0] = reinterpret_cast<float*>(fb + info_bytes(&p[i]));
+    d.xyb[1] = p[i].epf_iters > 0 ? reinterpret_cast<float*>(fb + info_bytes(&p[i]) + xyb_bytes(&p[i]))
+                                  : d.xyb[0];
+    const size_t stride = p[i].xsize;
+    jxlr_status st = make_info_args(ctx, &p[i], &io[i], info, &d.info);
+    if (!st) st = make_recon_args(ctx, &p[i], &io[i], info, d.xyb[0], stride, &d.rec);
+    if (!st && p[i].epf_iters > 0)
+      st = make_epf_args(ctx, &p[i], &io[i], info, d.xyb[0], d.xyb[1], stride, nullptr, nullptr,
+                         &d.epf);
+    if (!st) st = make_finish_args(ctx, &p[i], &io[i], d.xyb[0], stride, &d.fin);
+    if (st) return st;
+    d.epf_iters = p[i].epf_iters;
+    d.tiles_x = tiles_x(&p[i]);
+    tstart[i + 1] = tstart[i] + tiles_x(&p[i]) * tiles_y(&p[i]);
+    rstart[i + 1] = rstart[i] + regions_of(&p[i]);
+    max_epf = std::max(max_epf, p[i].epf_iters);
+  }
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return JXLR_E_HIP;
+  hipError_t e = hipMemcpy(base + L.frames, frames.data(), sizeof(FrameDesc) * n,
+                           hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(base + L.tile_start, tstart.data(), sizeof(int) * (n + 1), hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(base + L.region_start, rstart.data(), sizeof(int) * (n + 1),
+                  hipMemcpyHostToDevice);
+  if (e != hipSuccess) return JXLR_E_HIP;
+  plan->ws = ws;
+  plan->ws_bytes = L.total;
+  plan->n = n;
+  plan->total_tiles = tstart[n];
+  plan->total_regions = rstart[n];
+  plan->max_epf_iters = max_epf;
+  plan->frames_offset = L.frames;
+  plan->tile_start_offset = L.tile_start;
+  plan->region_start_offset = L.region_start;
+  return JXLR_OK;
+}
+
+jxlr_status jxlr_batch_run(jxlr_ctx* ctx, const jxlr_batch_plan* plan,
+                           const jxlr_launch_config* cfg, hipStream_t stream) {
+  jxlr_status st = check_plan(ctx, plan);
+  if (st) return st;
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return JXLR_E_HIP;
+  const jxlr_launch_config c = cfg ? *cfg : jxlr_launch_config{};
+  if ((st = launch_stage(ctx, plan, JXLR_STAGE_INFO, c.grid_info, 0, 0, stream))) return st;
+  if ((st = launch_stage(ctx, plan, JXLR_STAGE_RECON, c.grid_recon, c.order_recon, 0, stream)))
+    return st;
+  for (int k = 0; k < plan->max_epf_iters; ++k)
+    if ((st = launch_stage(ctx, plan, JXLR_STAGE_EPF, c.grid_epf, c.order_epf, k, stream)))
+      return st;
+  return launch_stage(ctx, plan, JXLR_STAGE_FINISH, c.grid_finish, c.order_finish, 0, stream);
+}
+
+jxlr_status jxlr_batch_stage(jxlr_ctx* ctx, const jxlr_batch_plan* plan, int stage, int grid,
+                             int order, int epf_pass, hipStream_t stream) {
+  jxlr_status st = check_plan(ctx, plan);
+  if (st) return st;
+  if (stage < 0 || stage > JXLR_STAGE_FINISH || order < 0 || order > 1 || epf_pass < 0 ||
+      (stage == JXLR_STAGE_EPF && epf_pass >= plan->max_epf_iters))
+    return JXLR_E_PARAM;
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return JXLR_E_HIP;
+  return launch_stage(ctx, plan, stage, grid, order, epf_pass, stream);
+}
+
+jxlr_status jxlr_autotune(jxlr_ctx* ctx, const jxlr_batch_plan* plan, int reps,
+                          jxlr_launch_config* best, float* best_ms, hipStream_t stream) {
+  jxlr_status st = check_plan(ctx, plan);
+  if (st) return st;
+  if (!best) return JXLR_E_NULL;
+  if (reps < 1 || reps > 1000) return JXLR_E_PARAM;
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return JXLR_E_HIP;
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device) !=
+      hipSuccess || cus <= 0)
+    return JXLR_E_HIP;
+  // one full run so that every buffer holds this batch's data; each stage
+  // alone is then idempotent and can be repeated for timing
+  if ((st = jxlr_batch_run(ctx, plan, nullptr, stream))) return st;
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return JXLR_E_HIP;
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return JXLR_E_HIP;
+  }
+  const int stages[3] = {JXLR_STAGE_RECON, JXLR_STAGE_EPF, JXLR_STAGE_FINISH};
+  const void* kerns[3] = {reinterpret_cast<const void*>(recon_batch_kernel),
+                          reinterpret_cast<const void*>(epf_batch_kernel),
+                          reinterpret_cast<const void*>(finish_batch_kernel)};
+  const int threads[3] = {kRecThreads, kThreads, kThreads};
+  jxlr_launch_config out{};
+  float total_ms = 0.0f;
+  for (int si = 0; si < 3 && !st; ++si) {
+    if (stages[si] == JXLR_STAGE_EPF && plan->max_epf_iters == 0) continue;
+    int occ = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kerns[si], threads[si], 0) !=
+            hipSuccess || occ <= 0)
+      occ = 1;
+    // candidates: one workgroup per tile, then persistent grids of 1..4 full
+    // waves of workgroups, each in both tile orders
+    std::vector<std::pair<int, int>> cand;
+    cand.push_back({plan->total_tiles, 0});
+    for (int k = 1; k <= 4; ++k) {
+      const int gsz = k * cus * occ;
+      if (gsz >= plan->total_tiles) break;
+      cand.push_back({gsz, 0});
+      cand.push_back({gsz & ~7, 1});
+    }
+    float best_t = 1e30f;
+    int bg = plan->total_tiles, bo = 0;
+    for (auto [gsz, order] : cand) {
+      if (gsz <= 0) continue;
+      // warm-up, then the best of three timed groups of `reps` launches
+      if ((st = launch_stage(ctx, plan, stages[si], gsz, order, 0, stream))) break;
+      float tmin = 1e30f;
+      for (int trial = 0; trial < 3 && !st; ++trial) {
+        if (hipEventRecord(e0, stream) != hipSuccess) { st = JXLR_E_HIP; break; }
+        for (int r = 0; r < reps && !st; ++r)
+          st = launch_stage(ctx, plan, stages[si], gsz, order, 0, stream);
+        float ms = 0.0f;
+        if (st || hipEventRecord(e1, stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+          if (!st) st = JXLR_E_HIP;
+          break;
+        }
+        tmin = std::min(tmin, ms / reps);
+      }
+      if (st) break;
+      if (tmin < best_t) {
+        best_t = tmin;
+        bg = gsz;
+        bo = order;
+      }
+    }
+    if (st) break;
+    const int mult = stages[si] == JXLR_STAGE_EPF ? plan->max_epf_iters : 1;
+    total_ms += best_t * mult;
+    if (stages[si] == JXLR_STAGE_RECON) { out.grid_recon = bg; out.order_recon = bo; }
+    if (stages[si] == JXLR_STAGE_EPF) { out.grid_epf = bg; out.order_epf = bo; }
+    if (stages[si] == JXLR_STAGE_FINISH) { out.grid_finish = bg; out.order_finish = bo; }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st) return st;
+  // leave the buffers as a full run leaves them
+  if ((st = jxlr_batch_run(ctx, plan, &out, stream))) return st;
+  *best = out;
+  if (best_ms) *best_ms = total_ms;
+  return JXLR_OK;
+}
+
+jxlr_status jxlr_decode_batch(jxlr_ctx* ctx, int n, const jxlr_frame_params* p,
+                              const jxlr_frame_io* io, void* ws, size_t ws_bytes,
+                              hipStream_t stream) {
+  jxlr_batch_plan plan;
+  jxlr_status st = jxlr_batch_prepare(ctx, n, p, io, ws, ws_bytes, &plan);
+  if (st) return st;
+  return jxlr_batch_run(ctx, &plan, nullptr, stream);
+}
+
+}  // extern "C"
+
+struct jxlr_graph {
+  int device;
+  hipGraph_t graph;
+  hipGraphExec_t exec;
+};
+
+extern "C" {
+
+jxlr_status jxlr_graph_create(jxlr_ctx* ctx, const jxlr_batch_plan* plan,
+                              const jxlr_launch_config* cfg, jxlr_graph** out) {
+  if (!ctx || !plan || !out) return JXLR_E_NULL;
+  *out = nullptr;
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return JXLR_E_HIP;
+  hipStream_t s;
+  if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return JXLR_E_HIP;
+  auto* gr = new jxlr_graph{ctx->device, nullptr, nullptr};
+  jxlr_status st = JXLR_OK;
+  if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) st = JXLR_E_HIP;
+  if (!st) {
+    st = jxlr_batch_run(ctx, plan, cfg, s);
+    if (hipStreamEndCapture(s, &gr->graph) != hipSuccess && !st) st = JXLR_E_HIP;
+  }
+  if (!st && hipGraphInstantiate(&gr->exec, gr->graph, nullptr, nullptr, 0) != hipSuccess)
+    st = JXLR_E_HIP;
+  (void)hipStreamDestroy(s);
+  if (st) {
+    jxlr_graph_destroy(gr);
+    return st;
+  }
+  *out = gr;
+  return JXLR_OK;
+}
+
+jxlr_status jxlr_graph_launch(jxlr_graph* gr, hipStream_t stream) {
+  if (!gr || !gr->exec) return JXLR_E_NULL;
+  DeviceGuard g(gr->device);
+  if (!g.ok) return JXLR_E_HIP;
+  return hipGraphLaunch(gr->exec, stream) == hipSuccess ? JXLR_OK : JXLR_E_HIP;
+}
+
+void jxlr_graph_destroy(jxlr_graph* gr) {
+  if (!gr) return;
+  DeviceGuard g(gr->device);
+  if (gr->exec) (void)hipGraphExecDestroy(gr->exec);
+  if (gr->graph) (void)hipGraphDestroy(gr->graph);
+  delete gr;
 }
 
 jxlr_status jxlr_get_device_status(jxlr_ctx* ctx, hipStream_t stream) {

@@ -11,6 +11,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <limits>
 #include <cstring>
 #include <vector>
 
@@ -257,6 +258,31 @@ void epf_mul_table(int sigma_shift, int32_t* table) {
   }
 }
 
+int srgb_code_f64(int bits, float v) {
+  // IEC 61966-2-1 encoding of the clamped linear value, then round half up
+  const double maxv = double((1 << bits) - 1);
+  double x = double(v);
+  x = x < 0.0 ? 0.0 : (x > 1.0 ? 1.0 : x);
+  const double e = x <= 0.0031308 ? 12.92 * x : 1.055 * std::pow(x, 1.0 / 2.4) - 0.055;
+  return int(std::floor(e * maxv + 0.5));
+}
+
+void srgb_thresholds(int bits, float* thr) {
+  const int maxv = (1 << bits) - 1;
+  thr[0] = -std::numeric_limits<float>::infinity();
+  thr[maxv + 1] = std::numeric_limits<float>::infinity();
+  for (int k = 1; k <= maxv; ++k) {
+    // start at the binary64 inverse of the boundary (k - 0.5) / maxv and walk
+    // to the first float whose code reaches k; codes are monotone in v
+    const double e = (k - 0.5) / maxv;
+    const double lin = e <= 12.92 * 0.0031308 ? e / 12.92 : std::pow((e + 0.055) / 1.055, 2.4);
+    float v = float(lin);
+    while (srgb_code_f64(bits, v) >= k) v = std::nextafter(v, -1.0f);
+    while (srgb_code_f64(bits, v) < k) v = std::nextafter(v, 2.0f);
+    thr[k] = v;
+  }
+}
+
 bool build_tables(DeviceTables* t) {
   std::memset(t, 0, sizeof(*t));
   std::vector<double> m(32 * 32);
@@ -283,6 +309,8 @@ bool build_tables(DeviceTables* t) {
         as[x * n + i] = float(v * transform_scale(8 * n, x));
       }
   }
+  srgb_thresholds(8, t->srgb_thr8);
+  srgb_thresholds(16, t->srgb_thr16);
   std::vector<double> dq(1024);
   for (int s = 0; s < kNumStrategies; ++s) {
     const int X = 8 * blocks_x(s), Y = 8 * blocks_y(s), sz = X * Y;

@@ -54,6 +54,13 @@ struct DeviceTables {
   // mul_table of J.2.4 for sigma 0..672 (entries below 16 unused), one per
   // kSigmaShift value 0..8.
   int32_t mul_table[9][673];
+  // Decision thresholds of the 8- and 16-bit outputs (sRGB transfer function
+  // of clamp(v, 0, 1), then floor(e (2^b - 1) + 0.5), evaluated in binary64):
+  // srgb_thrB[k], k = 1 .. 2^B - 1, is the smallest binary32 v whose code is
+  // at least k; entry 0 is -inf and entry 2^B is +inf.  The code of v is the
+  // c with srgb_thrB[c] <= v < srgb_thrB[c + 1].
+  float srgb_thr8[257];
+  float srgb_thr16[65537];
 };
 
 // Fills t on the host.  Returns false if a dequantization matrix entry is not
@@ -67,5 +74,9 @@ void inverse_transform_matrix_f64(int n, double* out);
 // coefficients multiplied by s_N(k).
 double transform_scale(int n, int k);
 void epf_mul_table(int sigma_shift, int32_t* table);
+// The output code of a binary32 sample, in binary64 (bits = 8 or 16).
+int srgb_code_f64(int bits, float v);
+// Fills thr[0 .. 2^bits] as described for DeviceTables::srgb_thr8/16.
+void srgb_thresholds(int bits, float* thr);
 
 }  // namespace jxlr

@@ -53,6 +53,28 @@ class FrameIO(C.Structure):
     ]
 
 
+class BatchPlan(C.Structure):
+    _fields_ = [
+        ("ws", C.c_void_p), ("ws_bytes", C.c_size_t),
+        ("n", C.c_int), ("total_tiles", C.c_int), ("total_regions", C.c_int),
+        ("max_epf_iters", C.c_int),
+        ("frames_offset", C.c_size_t), ("tile_start_offset", C.c_size_t),
+        ("region_start_offset", C.c_size_t),
+    ]
+
+
+class LaunchConfig(C.Structure):
+    _fields_ = [("grid_info", C.c_int), ("grid_recon", C.c_int), ("grid_epf", C.c_int),
+                ("grid_finish", C.c_int), ("order_recon", C.c_int), ("order_epf", C.c_int),
+                ("order_finish", C.c_int)]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
+STAGE_INFO, STAGE_RECON, STAGE_EPF, STAGE_FINISH = 0, 1, 2, 3
+
+
 class JxlrError(RuntimeError):
     def __init__(self, status, what=""):
         self.status = status
@@ -82,6 +104,21 @@ _SIGS = {
                       C.c_int),
     "jxlr_finish": ([C.c_void_p, C.POINTER(FrameParams), C.POINTER(FrameIO), C.c_void_p,
                      C.c_size_t, C.c_void_p], C.c_int),
+    "jxlr_batch_workspace_bytes": ([C.c_int, C.POINTER(FrameParams)], C.c_size_t),
+    "jxlr_batch_prepare": ([C.c_void_p, C.c_int, C.POINTER(FrameParams), C.POINTER(FrameIO),
+                            C.c_void_p, C.c_size_t, C.POINTER(BatchPlan)], C.c_int),
+    "jxlr_batch_run": ([C.c_void_p, C.POINTER(BatchPlan), C.POINTER(LaunchConfig), C.c_void_p],
+                       C.c_int),
+    "jxlr_batch_stage": ([C.c_void_p, C.POINTER(BatchPlan), C.c_int, C.c_int, C.c_int, C.c_int,
+                          C.c_void_p], C.c_int),
+    "jxlr_autotune": ([C.c_void_p, C.POINTER(BatchPlan), C.c_int, C.POINTER(LaunchConfig),
+                       C.POINTER(C.c_float), C.c_void_p], C.c_int),
+    "jxlr_decode_batch": ([C.c_void_p, C.c_int, C.POINTER(FrameParams), C.POINTER(FrameIO),
+                           C.c_void_p, C.c_size_t, C.c_void_p], C.c_int),
+    "jxlr_graph_create": ([C.c_void_p, C.POINTER(BatchPlan), C.POINTER(LaunchConfig),
+                          C.POINTER(C.c_void_p)], C.c_int),
+    "jxlr_graph_launch": ([C.c_void_p, C.c_void_p], C.c_int),
+    "jxlr_graph_destroy": ([C.c_void_p], None),
     "jxlr_get_device_status": ([C.c_void_p, C.c_void_p], C.c_int),
 }
 
@@ -142,6 +179,11 @@ def workspace_bytes(p):
     return lib().jxlr_workspace_bytes(C.byref(p))
 
 
+def batch_workspace_bytes(ps):
+    arr = (FrameParams * len(ps))(*ps)
+    return lib().jxlr_batch_workspace_bytes(len(ps), arr)
+
+
 def _stream_handle(stream):
     import torch
     s = stream if stream is not None else torch.cuda.current_stream()
@@ -162,6 +204,14 @@ class DeviceFrame:
         self.sharpness = t(frame["sharpness"], np.uint8)
         self.cfl_kx = t(frame["cfl_kx"], np.float32)
         self.cfl_kb = t(frame["cfl_kb"], np.float32)
+
+    def clone(self):
+        """A copy in distinct device memory."""
+        c = DeviceFrame.__new__(DeviceFrame)
+        c.xsize, c.ysize = self.xsize, self.ysize
+        for k in ("ac", "dc", "strategy", "qf", "sharpness", "cfl_kx", "cfl_kb"):
+            setattr(c, k, getattr(self, k).clone())
+        return c
 
     def io(self, out=None):
         io = FrameIO()
@@ -252,5 +302,77 @@ class Context:
         _check(lib().jxlr_decode(self.handle, C.byref(p), C.byref(io), ws.data_ptr(),
                                  ws.numel(), _stream_handle(stream)), "decode")
 
+    # --- batches ---
+    def batch_workspace(self, ps):
+        import torch
+        n = batch_workspace_bytes(ps)
+        if n == 0:
+            raise JxlrError(7, "batch_workspace_bytes")
+        return torch.empty(n, dtype=torch.uint8, device=f"cuda:{self.device}")
+
+    def batch_prepare(self, ps, ios, ws):
+        """ps, ios: lists of FrameParams / FrameIO; ws: device workspace tensor.
+        Returns the plan (keeps the host arrays alive with it)."""
+        n = len(ps)
+        parr = (FrameParams * n)(*ps)
+        iarr = (FrameIO * n)(*ios)
+        plan = BatchPlan()
+        _check(lib().jxlr_batch_prepare(self.handle, n, parr, iarr, ws.data_ptr(), ws.numel(),
+                                        C.byref(plan)), "batch_prepare")
+        return plan
+
+    def batch_run(self, plan, cfg=None, stream=None):
+        _check(lib().jxlr_batch_run(self.handle, C.byref(plan),
+                                    C.byref(cfg) if cfg is not None else None,
+                                    _stream_handle(stream)), "batch_run")
+
+    def batch_stage(self, plan, stage, grid=0, order=0, epf_pass=0, stream=None):
+        _check(lib().jxlr_batch_stage(self.handle, C.byref(plan), stage, grid, order, epf_pass,
+                                      _stream_handle(stream)), "batch_stage")
+
+    def autotune(self, plan, reps=5, stream=None):
+        """Returns (LaunchConfig, tuned ms per run)."""
+        cfg = LaunchConfig()
+        ms = C.c_float()
+        _check(lib().jxlr_autotune(self.handle, C.byref(plan), reps, C.byref(cfg), C.byref(ms),
+                                   _stream_handle(stream)), "autotune")
+        return cfg, float(ms.value)
+
+    def decode_batch(self, ps, ios, ws, stream=None):
+        n = len(ps)
+        parr = (FrameParams * n)(*ps)
+        iarr = (FrameIO * n)(*ios)
+        _check(lib().jxlr_decode_batch(self.handle, n, parr, iarr, ws.data_ptr(), ws.numel(),
+                                       _stream_handle(stream)), "decode_batch")
+
+    def graph(self, plan, cfg=None):
+        return Graph(self, plan, cfg)
+
     def device_status(self, stream=None):
         return lib().jxlr_get_device_status(self.handle, _stream_handle(stream))
+
+
+class Graph:
+    """A prepared batch captured into a HIP graph (jxlr_graph_*)."""
+
+    def __init__(self, ctx, plan, cfg=None):
+        self.ctx = ctx
+        h = C.c_void_p()
+        _check(lib().jxlr_graph_create(ctx.handle, C.byref(plan),
+                                       C.byref(cfg) if cfg is not None else None, C.byref(h)),
+               "graph_create")
+        self.handle = h
+
+    def launch(self, stream=None):
+        _check(lib().jxlr_graph_launch(self.handle, _stream_handle(stream)), "graph_launch")
+
+    def close(self):
+        if self.handle:
+            lib().jxlr_graph_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -97,3 +97,27 @@ def compare_rgb(p, gpu, orc):
                 max_err_affected=float(err[:, mask].max()) if mask.any() else 0.0,
                 affected=int(mask.sum()), pixels=int(mask.size), passes=stats,
                 max_abs_ref=float(np.abs(orc["rgb"]).max()))
+
+
+def srgb_codes_check(p, codes, orc, gpu_epf, bits):
+    """Compares 8/16-bit output codes with the oracle's rounding (sRGB OETF,
+    then round half up).  Returns (n_firm_equal, n_firm, max_code_diff): codes
+    must equal where the oracle's pre-rounding value is not within the FP32
+    error bound of a rounding boundary and no EPF decision differs; elsewhere
+    (outside flip-affected pixels) a neighbouring code is allowed."""
+    from oracle import oracle as O
+    codes = np.asarray(codes).astype(np.int64)
+    lin = orc["rgb"]
+    ref = O.quantize_srgb(bits, lin).astype(np.int64)
+    maxv = (1 << bits) - 1
+    v = np.clip(lin, 0, 1)
+    e = np.where(v <= 0.0031308, 12.92 * v, 1.055 * np.power(v, 1 / 2.4) - 0.055) * maxv + 0.5
+    frac = e - np.floor(e)
+    near = np.minimum(frac, 1 - frac) < maxv * RGB_TOL * 13 + 1e-3  # OETF slope <= 12.92
+    mask, _ = affected_mask(p, [(g, s) for _, g, s in gpu_epf], [(g, s) for _, g, s in orc["epf"]])
+    if p.gab:
+        mask = dilate(mask, range(-1, 2), range(-1, 2))
+    firm = ~near & ~mask[None]
+    diff = np.abs(codes - ref)[~mask[None].repeat(3, 0)]
+    return (int((codes[firm] == ref[firm]).sum()), int(firm.sum()),
+            int(diff.max()) if diff.size else 0)

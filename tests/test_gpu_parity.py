@@ -139,6 +139,34 @@ def test_srgb_output_codes(ctx, fmt, bits):
     print(f"{bits}-bit: {firm.mean():.4f} of samples exact-checked")
 
 
+@pytest.mark.parametrize("bits,fmt", [(8, 1), (16, 2)])
+@pytest.mark.parametrize("seed", [31, 32])
+def test_quantized_output_is_oracle_rounding_of_same_values(ctx, bits, fmt, seed):
+    """The 8/16-bit codes are exactly the oracle's binary64 rounding (sRGB
+    transfer, round half up) of the linear values the same path exports in
+    binary32, on every sample, including those close to a code boundary."""
+    from paper_1908_03565_amd import jxlr as J
+    f = wl.small(200, 136, seed=seed)
+    p32 = J.params(f["xsize"], f["ysize"], out_format=0, **f["params"])
+    pq = J.params(f["xsize"], f["ysize"], out_format=fmt, **f["params"])
+    df = J.DeviceFrame(f)
+    lin = ctx.empty_out(p32)
+    codes = ctx.empty_out(pq)
+    ctx.decode(p32, df, lin, ctx.workspace(p32))
+    ctx.decode(pq, df, codes, ctx.workspace(pq))
+    lin = lin.cpu().numpy().astype(np.float64)
+    got = codes.cpu().numpy().astype(np.int64)
+    ref = O.quantize_srgb(bits, lin).astype(np.int64)
+    assert np.array_equal(got, ref), int((got != ref).sum())
+    # samples whose binary32 estimate alone would have been ambiguous
+    e = np.clip(lin, 0, 1)
+    e = np.where(e <= 0.0031308, 12.92 * e, 1.055 * np.power(e, 1 / 2.4) - 0.055)
+    frac = e * ((1 << bits) - 1) + 0.5
+    near = np.abs(frac - np.round(frac)) < 1e-3
+    print(f"{bits}-bit seed {seed}: {got.size} samples exact, {int(near.sum())} within 1e-3 code "
+          "of a boundary")
+
+
 def test_dc_only_frame_is_constant_per_varblock(ctx):
     """A varblock whose DC samples are all equal and whose AC is zero decodes
     to that constant (I.2.7 inverting I.2.6), for every transform type."""

@@ -97,6 +97,18 @@ def test_workspace_bytes():
     assert J.workspace_bytes(p2) % 256 == 0
 
 
+def test_batch_workspace_bytes():
+    # header (descriptors and two prefix arrays) plus each frame's single-frame
+    # workspace, so a batch of one needs more than jxlr_workspace_bytes alone
+    ps = [J.params(100, 50, epf_iters=0), J.params(256, 256, epf_iters=2), J.params(8, 8)]
+    total = J.batch_workspace_bytes(ps)
+    assert total % 256 == 0
+    assert total > sum(J.workspace_bytes(p) for p in ps)
+    assert J.batch_workspace_bytes(ps[:1]) > J.workspace_bytes(ps[0])
+    assert J.batch_workspace_bytes([]) == 0
+    assert J.batch_workspace_bytes(ps + [J.params(64, 64, epf_iters=4)]) == 0
+
+
 # --- the library's constant tables versus the oracle's --------------------
 
 @pytest.fixture(scope="module")
@@ -111,6 +123,7 @@ def shim(tmp_path_factory):
               "shim_dqs", "shim_a16s", "shim_a32s"):
         getattr(L, f).restype = C.POINTER(C.c_float)
     L.shim_mul.restype = C.POINTER(C.c_int32)
+    L.shim_thr.restype = C.POINTER(C.c_float)
     assert L.shim_build() == 1
     return L
 
@@ -195,3 +208,31 @@ def test_prescaled_tables_match_oracle(shim):
         ref = np.stack([O.llf_from_dc(s, e.reshape(1, n)).ravel() for e in np.eye(n)], axis=1)
         ref = ref * _col_scale(8 * n)[:n, None]
         np.testing.assert_allclose(a, ref, atol=2e-7)
+
+
+def test_schedule_cache_roundtrip(tmp_path):
+    from paper_1908_03565_amd import tuning
+    path = str(tmp_path / "d" / "s.json")
+    assert tuning._load(path) == {}
+    tuning._store(path, {"k": {"grid_recon": 3}})
+    assert tuning._load(path) == {"k": {"grid_recon": 3}}
+    plan = J.BatchPlan()
+    plan.total_tiles, plan.max_epf_iters = 1000, 2
+    assert tuning.batch_key("dev", plan) == "dev|tiles~1024|epf2"
+    open(path, "w").write("not json")
+    assert tuning._load(path) == {}
+
+
+@pytest.mark.parametrize("bits", [8, 16])
+def test_srgb_thresholds_match_oracle_rounding(shim, bits):
+    # thr[k] is the first binary32 value the oracle's binary64 rounding sends
+    # to code k, and the float just below it goes to k - 1
+    maxv = (1 << bits) - 1
+    thr = _arr(shim.shim_thr(bits), maxv + 2)
+    assert thr[0] == -np.inf and thr[-1] == np.inf
+    t = thr[1:-1].astype(np.float32)
+    below = np.nextafter(t, np.float32(-1))
+    k = np.arange(1, maxv + 1)
+    assert np.all(np.diff(t) > 0)
+    np.testing.assert_array_equal(O.quantize_srgb(bits, t.astype(np.float64)), k)
+    np.testing.assert_array_equal(O.quantize_srgb(bits, below.astype(np.float64)), k - 1)
