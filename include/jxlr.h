@@ -93,6 +93,13 @@ typedef struct {
   float    opsin_bias[3];      /* opsin biases (L.2, C.4.9) */
   int32_t  target_nits_div50;  /* ImageMetadata (A.4.5), >= 1 */
   int32_t  out_format;         /* jxlr_out_format */
+  /* Inverse-transform arithmetic.  0: binary32 throughout (the plain form).
+   * 1: split precision, for every 32x32 region tiled by varblocks of one
+   * DCT type (DCT8, DCT16, DCT32 and the rectangular DCTs): each pass is a
+   * matrix product on the matrix cores with operands split into bfloat16
+   * high and low parts, hi*hi + hi*lo + lo*hi accumulated in binary32; other
+   * regions use the plain form. */
+  int32_t  idct_split;
 } jxlr_frame_params;
 
 /* Input and output planes of one frame.  With Wb = ceil(xsize/8),
@@ -219,7 +226,7 @@ typedef struct jxlr_batch_plan {
   int total_tiles;   /* 64x32 pixel tiles over all frames */
   int total_regions; /* 32x32 DctSelect regions over all frames */
   int max_epf_iters;
-  size_t frames_offset, tile_start_offset, region_start_offset;
+  size_t frames_offset, tile_frame_offset, tile_start_offset, region_start_offset;
 } jxlr_batch_plan;
 
 /* Schedule of the four persistent stage kernels.  grid_*: workgroup count;

@@ -223,6 +223,9 @@ struct ReconArgs {
   size_t xyb_stride;
   int* status;
   const DeviceTables* __restrict__ tab;
+  int split;        // split-precision matrix-core transform of uniform regions
+  int ac_vec;       // AC planes and stride allow 16-byte loads
+  int xyb_vec;      // XYB planes and stride allow 16-byte stores
 };
 
 // Plain N-point DCT-III in registers, y_n = sum_k x_k cos(pi (2n + 1) k / (2N)),
@@ -317,6 +320,77 @@ __device__ inline int dq_off_lut(int s) {
   return int(v & 0xFFu) * 192;
 }
 
+// ---- split-precision matrix-core transform --------------------------------
+// A 32x32 region tiled by varblocks of one DCT type is transformed as two
+// matrix products, columns Y = A_col K and rows S = Y A_row^T, with A the
+// block-diagonal plain DCT-III matrix of the varblock height / width.  Each
+// product runs on v_mfma_f32_32x32x16_bf16: both operands are split into a
+// bfloat16 high part and a bfloat16 rest, and hi*hi + hi*lo + lo*hi is
+// accumulated in binary32 (the dropped lo*lo term is below 2^-16 of each
+// product).  Operand layouts of the instruction (one wave): lane l supplies
+// A[l mod 32][8 (l / 32) + e] and B[8 (l / 32) + e][l mod 32], e < 8, and
+// accumulator q of lane l is C[8 (q / 4) + 4 (l / 32) + q mod 4][l mod 32].
+
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef short s16x8 __attribute__((ext_vector_type(8)));
+typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
+
+__device__ inline uint32_t bf16_bits(float x) {
+  const uint32_t u = __float_as_uint(x);
+  return (u + 0x7FFFu + ((u >> 16) & 1u)) >> 16;  // round to nearest even
+}
+
+// One wave transforms the 32x32 block of cf starting at column col0, in
+// place.  Acol / Arow: the DeviceTables::mfma_a operands [part][step][lane][8]
+// of the column and row matrices.  Every wave of the workgroup calls this
+// the same number of times (it holds workgroup barriers).
+__device__ inline void mfma_region(float (*cf)[kRecLd], int col0, const uint16_t* __restrict__ Acol,
+                                   const uint16_t* __restrict__ Arow, int lane) {
+  const int j = lane & 31, kh = lane >> 5;
+#pragma unroll
+  for (int pass = 0; pass < 2; ++pass) {
+    const uint16_t* A = pass == 0 ? Acol : Arow;
+    f32x16 acc;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) acc[q] = 0.0f;
+#pragma unroll
+    for (int step = 0; step < 2; ++step) {
+      const bf16x8 ah = *reinterpret_cast<const bf16x8*>(A + ((0 * 2 + step) * 64 + lane) * 8);
+      const bf16x8 al = *reinterpret_cast<const bf16x8*>(A + ((1 * 2 + step) * 64 + lane) * 8);
+      s16x8 bh, bl;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int k = 16 * step + 8 * kh + e;
+        // pass 0: B = K[k][j]; pass 1: B = Y^T[k][j] = Y[j][k]
+        const float v = pass == 0 ? cf[k][col0 + j] : cf[j][col0 + k];
+        const uint32_t h = bf16_bits(v);
+        bh[e] = short(h);
+        bl[e] = short(bf16_bits(v - __uint_as_float(h << 16)));
+      }
+      const bf16x8 bH = __builtin_bit_cast(bf16x8, bh), bL = __builtin_bit_cast(bf16x8, bl);
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bH, acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bL, acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bH, acc, 0, 0, 0);
+    }
+    __syncthreads();  // every lane has read its operands
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int i = 8 * (q >> 2) + 4 * kh + (q & 3);
+      // pass 0: Y[i][j]; pass 1: S^T[i][j] = S[j][i]
+      if (pass == 0) cf[i][col0 + j] = acc[q];
+      else cf[j][col0 + i] = acc[q];
+    }
+    __syncthreads();
+  }
+}
+
+// Coefficient groups of a tile: 4 horizontally adjacent positions (inside one
+// 8x8 block) in all three channels; 16 groups per tile row, 512 per tile.
+// Thread t takes groups t, t + 192 and t + 384 (the last only for t < 128).
+constexpr int kRecGroups = kRecTW / 4 * kRecTH;
+static_assert(offsetof(DeviceTables, dqs) % 16 == 0, "16-byte loads of dequantization weights");
+constexpr int kRecGPT = (kRecGroups + kRecThreads - 1) / kRecThreads;
+
 // One 64x32 tile (tile column tbx, row tby) of the reconstruction.
 __device__ inline void recon_tile(const ReconArgs& a, int tbx, int tby) {
   __shared__ float coef[3][kRecTH][kRecLd];
@@ -328,12 +402,40 @@ __device__ inline void recon_tile(const ReconArgs& a, int tbx, int tby) {
   __shared__ float s_llw[3][4][4];
   __shared__ uint8_t s_owner[2][16], s_strat[2][16];
   __shared__ int s_bad[2];
+  // per region: operand selectors (column matrix | row matrix << 2) of the
+  // split-precision transform, or -1 for the binary32 passes
+  __shared__ int s_mma[2];
 
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
   const int x0 = kRecTW * tbx, y0 = kRecTH * tby;
   const int gbx0 = x0 / 8, gby0 = y0 / 8;
   const DeviceTables* __restrict__ T = a.tab;
+
+  // The quantized AC of this thread's groups, loaded before anything else
+  // (the addresses do not depend on the varblock map).  Groups outside the
+  // coefficient planes read the planes' first group and are not used.
+  int4 q[kRecGPT][3];
+  {
+    const int cw = 8 * a.Wb, ch = 8 * a.Hb;
+    const bool vec = a.ac_vec;
+#pragma unroll
+    for (int k = 0; k < kRecGPT; ++k) {
+      const int g = tid + kRecThreads * k;
+      const int Y = g >> 4, X = 4 * (g & 15);
+      const bool in = g < kRecGroups && x0 + X < cw && y0 + Y < ch;
+      const size_t off = in ? size_t(y0 + Y) * a.ac_stride + x0 + X : 0;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const int32_t* src = a.ac[c] + off;
+        if (vec) {
+          q[k][c] = *reinterpret_cast<const int4*>(src);
+        } else {
+          q[k][c] = make_int4(src[0], src[1], src[2], src[3]);
+        }
+      }
+    }
+  }
 
   if (tid < 2) s_bad[tid] = 0;
   if (tid >= 64 && tid < 112) {
@@ -344,8 +446,11 @@ __device__ inline void recon_tile(const ReconArgs& a, int tbx, int tby) {
     else w = T->a32s[x * 4 + i];
     s_llw[sz][x][i] = w;
   }
-  if (tid >= 128 && tid < 128 + 96) {
-    const int k = tid - 128;
+  // the last 96 threads clear the padding of all three channels (the LLF
+  // window reads it with zero weights, and 0 * NaN is NaN)
+  static_assert(kRecThreads >= 96, "padding clear needs 96 threads");
+  if (tid >= kRecThreads - 96) {
+    const int k = tid - (kRecThreads - 96);
     s_dc[k / 32][32 + (k & 31)] = 0.0f;
   }
   __syncthreads();
@@ -370,89 +475,89 @@ __device__ inline void recon_tile(const ReconArgs& a, int tbx, int tby) {
     s_dc[2][tid] = in ? fmaf(a.kb_dc, y_, b_) : 0.0f;
   }
   __syncthreads();
-  if (tid < 2 && s_bad[tid]) {
-    for (int i = 0; i < 16; ++i) s_strat[tid][i] = kAbsent;
+  if (tid < 2) {
+    if (s_bad[tid])
+      for (int i = 0; i < 16; ++i) s_strat[tid][i] = kAbsent;
+    int m = -1;
+    if (a.split) {
+      // one DCT type over the whole region (then its varblocks tile it)
+      const int s0 = s_strat[tid][0];
+      bool uni = s0 != kAbsent && s0 != 1 && s0 != 2 && s0 != 3;
+      for (int i = 1; i < 16; ++i) uni = uni && s_strat[tid][i] == s0;
+      if (uni) m = (vb_by(s0) >> 1) | ((vb_bx(s0) >> 1) << 2);
+    }
+    s_mma[tid] = m;
   }
   __syncthreads();
 
-  // F.3 dequantization, I.2.7 LLF from DC, Annex G chroma from luma; the
-  // tables carry the transform scales (the passes below are plain DCT-III).
-  // Wave w takes tile rows w, w + 3, ... (11 rows at most); lane = tile
-  // column.  All global loads of the lane's rows are issued before any
-  // arithmetic; rows outside the frame or in ill-formed regions load the
-  // tile's first coefficient and are not stored.
+  // F.3 dequantization and Annex G chroma from luma of the thread's groups;
+  // the tables carry the transform scales (the passes below are plain
+  // DCT-III).  LLF positions get a value here too and are overwritten next.
   {
-    constexpr int kRows = 11;
-    const int X = lane, r = X >> 5, bxl = X >> 3;
     const size_t tile = size_t(y0 / 64) * a.cfl_stride + x0 / 64;
     const float kx = a.cfl_kx[tile], kb = a.cfl_kb[tile];
-    int rs[kRows], ro[kRows], rdq[kRows];
-    int q[kRows][3];
-    float dqv[kRows][3];
 #pragma unroll
-    for (int k = 0; k < kRows; ++k) {
-      const int Y = min(wave + 3 * k, kRecTH - 1);
-      const int lb = (Y >> 3) * 4 + (bxl & 3);
-      int s = s_strat[r][lb];
-      if (wave + 3 * k >= kRecTH) s = kAbsent;
-      const int o = s_owner[r][lb];
-      const int x = (X & 31) - 8 * (o & 3), y = Y - 8 * (o >> 2);
-      const bool hf = s != kAbsent && !(x < vb_bx(s) && y < vb_by(s));
-      const int sz = 64 * vb_bx(s) * vb_by(s);
-      rs[k] = s;
-      ro[k] = o;
-      rdq[k] = hf ? dq_off_lut(s) + y * 8 * vb_bx(s) + x : 0;
-      const size_t g = hf ? size_t(y0 + Y) * a.ac_stride + x0 + X : size_t(y0) * a.ac_stride + x0;
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        q[k][c] = a.ac[c][g];
-        dqv[k][c] = T->dqs[rdq[k] + (hf ? c * sz : 0)];
-      }
-    }
-#pragma unroll
-    for (int k = 0; k < kRows; ++k) {
-      const int Y = wave + 3 * k;
-      const int s = rs[k];
+    for (int k = 0; k < kRecGPT; ++k) {
+      const int g = tid + kRecThreads * k;
+      if (g >= kRecGroups) break;
+      const int Y = g >> 4, X = 4 * (g & 15), r = X >> 5;
+      const int lb = (Y >> 3) * 4 + ((X & 31) >> 3);
+      const int s = s_strat[r][lb];
       if (s == kAbsent) continue;
-      const int o = ro[k];
+      const int o = s_owner[r][lb];
       const int ob = (o >> 2) * 8 + 4 * r + (o & 3);  // the varblock's top-left tile block
       const int x = (X & 31) - 8 * (o & 3), y = Y - 8 * (o >> 2);
-      const int cxb = vb_bx(s), cyb = vb_by(s);
-      float K[3];
-      if (x < cxb && y < cyb) {
-        const int sx = cxb == 4 ? 2 : cxb - 1, sy = cyb == 4 ? 2 : cyb - 1;
-        float fx[4], fy[4];
+      const int sz = 64 * vb_bx(s) * vb_by(s);
+      const float* dq = T->dqs + dq_off_lut(s) + y * 8 * vb_bx(s) + x;
+      const float acm = s_acmul[ob];
+      float K[3][4];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          fx[i] = s_llw[sx][x][i];
-          fy[i] = s_llw[sy][y][i];
+      for (int c = 0; c < 3; ++c) {
+        const float4 w = *reinterpret_cast<const float4*>(dq + c * sz);
+        const int qq[4] = {q[k][c].x, q[k][c].y, q[k][c].z, q[k][c].w};
+        const float wv[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const float fq = float(qq[e]);
+          // 0.145 / q through the hardware reciprocal (1 ulp)
+          const float bq = (qq[e] >= -1 && qq[e] <= 1) ? fq * a.one_bias[c]
+                                                       : fmaf(-0.145f, __builtin_amdgcn_rcpf(fq), fq);
+          K[c][e] = bq * acm * wv[e];
         }
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          float acc = 0.0f;
-#pragma unroll
-          for (int jy = 0; jy < 4; ++jy) {
-            float row = 0.0f;
-#pragma unroll
-            for (int ix = 0; ix < 4; ++ix) row = fmaf(fx[ix], s_dc[c][ob + 8 * jy + ix], row);
-            acc = fmaf(fy[jy], row, acc);
-          }
-          K[c] = acc;
-        }
-      } else {
-        const float acm = s_acmul[ob];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          const int qq = q[k][c];
-          const float fq = float(qq);
-          const float bq = (qq >= -1 && qq <= 1) ? fq * a.one_bias[c] : fq - 0.145f / fq;
-          K[c] = bq * acm * dqv[k][c];
-        }
-        K[0] = fmaf(kx, K[1], K[0]);
-        K[2] = fmaf(kb, K[1], K[2]);
       }
 #pragma unroll
-      for (int c = 0; c < 3; ++c) coef[c][Y][X] = K[c];
+      for (int e = 0; e < 4; ++e) {
+        coef[0][Y][X + e] = fmaf(kx, K[1][e], K[0][e]);
+        coef[1][Y][X + e] = K[1][e];
+        coef[2][Y][X + e] = fmaf(kb, K[1][e], K[2][e]);
+      }
+    }
+  }
+  __syncthreads();
+
+  // I.2.7 LLF from DC: tile block b of a varblock holds the varblock's LLF
+  // coefficient (column, row) = the block's offset inside the varblock (8x8
+  // types: the DC itself).  One thread per block and channel.
+  if (tid < 96) {
+    const int c = tid >> 5, b = tid & 31;
+    const int bxl = b & 7, byl = b >> 3, r = bxl >> 2, lb = byl * 4 + (bxl & 3);
+    const int s = s_strat[r][lb];
+    if (s != kAbsent) {
+      const int o = s_owner[r][lb];
+      const int ox = o & 3, oy = o >> 2;
+      const int dx = (bxl & 3) - ox, dy = byl - oy;
+      const int ob = oy * 8 + 4 * r + ox;
+      const int cxb = vb_bx(s), cyb = vb_by(s);
+      const int sx = cxb == 4 ? 2 : cxb - 1, sy = cyb == 4 ? 2 : cyb - 1;
+      float acc = 0.0f;
+#pragma unroll
+      for (int jy = 0; jy < 4; ++jy) {
+        float row = 0.0f;
+#pragma unroll
+        for (int ix = 0; ix < 4; ++ix) row = fmaf(s_llw[sx][dx][ix], s_dc[c][ob + 8 * jy + ix], row);
+        acc = fmaf(s_llw[sy][dy][jy], row, acc);
+      }
+      coef[c][8 * oy + dy][32 * r + 8 * ox + dx] = acc;
     }
   }
   __syncthreads();
@@ -493,7 +598,8 @@ __device__ inline void recon_tile(const ReconArgs& a, int tbx, int tby) {
     for (int br = 0; br < 4; ++br) {
       const int lb = br * 4 + ((X & 31) >> 3);
       const int s = s_strat[r][lb];
-      if (s == kAbsent || s == 1 || s == 2 || (s_owner[r][lb] >> 2) != br) continue;
+      if (s == kAbsent || s == 1 || s == 2 || (s_owner[r][lb] >> 2) != br || s_mma[r] >= 0)
+        continue;
       segment(&coef[c][8 * br][X], kRecLd, s, 8 * vb_by(s));
     }
   }
@@ -505,23 +611,46 @@ __device__ inline void recon_tile(const ReconArgs& a, int tbx, int tby) {
     for (int bc = 0; bc < 4; ++bc) {
       const int lb = (Y >> 3) * 4 + bc;
       const int s = s_strat[r][lb];
-      if (s == kAbsent || s == 1 || s == 2 || (s_owner[r][lb] & 3) != bc) continue;
+      if (s == kAbsent || s == 1 || s == 2 || (s_owner[r][lb] & 3) != bc || s_mma[r] >= 0)
+        continue;
       segment(&coef[c][Y][32 * r + 8 * bc], 1, s, 8 * vb_bx(s));
     }
   }
   __syncthreads();
 
-  // Crop (6.2) and store; an ill-formed region is written as zero.
+  // Split-precision transform of the uniform regions (wave = channel).
+  if (a.split) {
+    for (int r = 0; r < 2; ++r) {
+      const int m = s_mma[r];
+      if (m < 0) continue;
+      mfma_region(coef[wave], 32 * r, &T->mfma_a[m & 3][0][0][0][0], &T->mfma_a[m >> 2][0][0][0][0],
+                  lane);
+    }
+  }
+
+  // Crop (6.2) and store, the thread's groups again; an ill-formed region is
+  // written as zero.
   {
-    const int X = lane, gx = x0 + X;
-    const bool ok = !s_bad[X >> 5];
-    if (gx < a.W)
-      for (int Y = wave; Y < kRecTH; Y += 3) {
-        const int gy = y0 + Y;
-        if (gy >= a.H) break;
-        for (int c = 0; c < 3; ++c)
-          a.xyb[(size_t(c) * a.H + gy) * a.xyb_stride + gx] = ok ? coef[c][Y][X] : 0.0f;
+#pragma unroll
+    for (int k = 0; k < kRecGPT; ++k) {
+      const int g = tid + kRecThreads * k;
+      if (g >= kRecGroups) break;
+      const int Y = g >> 4, X = 4 * (g & 15), gx = x0 + X, gy = y0 + Y;
+      if (gx >= a.W || gy >= a.H) continue;
+      const bool ok = !s_bad[X >> 5];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        float v[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) v[e] = ok ? coef[c][Y][X + e] : 0.0f;
+        float* dst = a.xyb + (size_t(c) * a.H + gy) * a.xyb_stride + gx;
+        if (a.xyb_vec && gx + 4 <= a.W) {
+          *reinterpret_cast<float4*>(dst) = make_float4(v[0], v[1], v[2], v[3]);
+        } else {
+          for (int e = 0; e < 4 && gx + e < a.W; ++e) dst[e] = v[e];
+        }
       }
+    }
   }
 }
 
@@ -794,15 +923,19 @@ struct FinishArgs {
   const float* thr;  // decision thresholds of the 8- or 16-bit code
 };
 
+// sRGB transfer function of the clamped value, as an estimate: the power
+// goes through the hardware base-2 logarithm and exponential (about 1e-6
+// relative), close enough for srgb_code to settle the exact code.
 __device__ inline float srgb_encode(float v) {
   v = fminf(fmaxf(v, 0.0f), 1.0f);
-  return v <= 0.0031308f ? 12.92f * v : 1.055f * powf(v, 1.0f / 2.4f) - 0.055f;
+  const float p = __builtin_amdgcn_exp2f(__builtin_amdgcn_logf(v) * (1.0f / 2.4f));
+  return v <= 0.0031308f ? 12.92f * v : fmaf(1.055f, p, -0.055f);
 }
 
 // Output code of a linear sample, identical to the binary64 definition
-// (sRGB transfer of the clamped value, round half up): the binary32 estimate
-// is within one code of it, and the thresholds (the smallest binary32 value
-// of each code, computed in binary64 on the host) settle the last step.
+// (sRGB transfer of the clamped value, round half up): the estimate is
+// within one code of it, and the thresholds (the smallest binary32 value of
+// each code, computed in binary64 on the host) settle the last step.
 __device__ inline int srgb_code(float v, const float* __restrict__ thr, int maxv) {
   int c = int(floorf(srgb_encode(v) * float(maxv) + 0.5f));
   c = min(max(c, 0), maxv);
@@ -811,51 +944,111 @@ __device__ inline int srgb_code(float v, const float* __restrict__ thr, int maxv
   return c;
 }
 
-__device__ inline void finish_pixel(const FinishArgs& a, int x, int y) {
-  const size_t plane = size_t(a.H) * a.stride;
-  float v[3];
-  if (a.gab) {
-    const int xm = mirror(x - 1, a.W), xp = mirror(x + 1, a.W);
-    const int ym = mirror(y - 1, a.H), yp = mirror(y + 1, a.H);
-    for (int c = 0; c < 3; ++c) {
-      const float* p = a.in + c * plane;
-      const float* rm = p + size_t(ym) * a.stride;
-      const float* r0 = p + size_t(y) * a.stride;
-      const float* rp = p + size_t(yp) * a.stride;
-      const float edge = (rm[x] + r0[xm]) + (r0[xp] + rp[x]);
-      const float corner = (rm[xm] + rm[xp]) + (rp[xm] + rp[xp]);
-      v[c] = fmaf(a.k0[c], r0[x], fmaf(a.k1[c], edge, a.k2[c] * corner));
-    }
-  } else {
-    for (int c = 0; c < 3; ++c) v[c] = a.in[c * plane + size_t(y) * a.stride + x];
-  }
+// XYB -> RGB (L.2) of one pixel (v: X, Y, B after Gaborish) and its store at
+// element offset o of the output planes o0..o2, in the output format.
+__device__ inline void finish_store1(const FinishArgs& a, const float (&v)[3], void* o0, void* o1,
+                                     void* o2, size_t o, const float* thr) {
   const float gr = v[1] + v[0], gg = v[1] - v[0], gb = v[2];
   const float mr = fmaf(gr * gr, gr, a.bias[0]);
   const float mg = fmaf(gg * gg, gg, a.bias[1]);
   const float mb = fmaf(gb * gb, gb, a.bias[2]);
   float rgb[3];
-  for (int r = 0; r < 3; ++r)
-    rgb[r] = fmaf(a.m[3 * r], mr, fmaf(a.m[3 * r + 1], mg, a.m[3 * r + 2] * mb));
-  const size_t o = size_t(y) * a.out_stride + x;
+#pragma unroll
+  for (int r = 0; r < 3; ++r) rgb[r] = fmaf(a.m[3 * r], mr, fmaf(a.m[3 * r + 1], mg, a.m[3 * r + 2] * mb));
+  void* dst[3] = {o0, o1, o2};
   if (a.format == JXLR_OUT_F32) {
-    for (int c = 0; c < 3; ++c) static_cast<float*>(a.out[c])[o] = rgb[c];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) static_cast<float*>(dst[c])[o] = rgb[c];
   } else if (a.format == JXLR_OUT_U8_SRGB) {
-    for (int c = 0; c < 3; ++c) static_cast<uint8_t*>(a.out[c])[o] = uint8_t(srgb_code(rgb[c], a.thr, 255));
+#pragma unroll
+    for (int c = 0; c < 3; ++c) static_cast<uint8_t*>(dst[c])[o] = uint8_t(srgb_code(rgb[c], thr, 255));
   } else {
+#pragma unroll
     for (int c = 0; c < 3; ++c)
-      static_cast<uint16_t*>(a.out[c])[o] = uint16_t(srgb_code(rgb[c], a.thr, 65535));
+      static_cast<uint16_t*>(dst[c])[o] = uint16_t(srgb_code(rgb[c], thr, 65535));
   }
 }
 
-// One 64x32 tile: thread = column, rows threadIdx.x / 64 + 4 k.
-__device__ inline void finish_tile(const FinishArgs& a, int tbx, int tby) {
-  const int x = 64 * tbx + (threadIdx.x & 63);
-  if (x >= a.W) return;
-  for (int k = 0; k < 8; ++k) {
-    const int y = 32 * tby + (threadIdx.x >> 6) + 4 * k;
-    if (y >= a.H) break;
-    finish_pixel(a, x, y);
+// Output rows per finish thread; a 64x32 tile takes 64 * 32 / kFinRows
+// threads.
+#ifndef JXLR_FIN_ROWS
+#define JXLR_FIN_ROWS 4
+#endif
+constexpr int kFinRows = JXLR_FIN_ROWS;
+constexpr int kFinThreads = 64 * 32 / kFinRows;
+
+// One thread's strip: column x, output rows ys .. ys + nrows - 1 (nrows <=
+// kFinRows); gx / gy: the (mirrored) input columns x - 1 .. x + 1 and rows
+// ys - 1 .. ys + kFinRows.  The input and output planes are distinct buffers; saying so lets
+// the compiler issue the loads of later rows ahead of earlier stores.
+__device__ inline void finish_strip(const FinishArgs& a, const float* __restrict__ in,
+                                    void* __restrict__ o0, void* __restrict__ o1,
+                                    void* __restrict__ o2, const float* thr, int x,
+                                    const int (&gx)[3], const int (&gy)[kFinRows + 2], int ys,
+                                    int nrows) {
+  const size_t plane = size_t(a.H) * a.stride;
+  const size_t ob = size_t(ys) * a.out_stride + x;
+  if (!a.gab) {
+#pragma unroll
+    for (int r = 0; r < kFinRows; ++r) {
+      if (r >= nrows) break;
+      float v[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) v[c] = in[c * plane + size_t(gy[r + 1]) * a.stride + x];
+      finish_store1(a, v, o0, o1, o2, ob + size_t(r) * a.out_stride, thr);
+    }
+    return;
   }
+  float w[3][3][3];  // rolling rows [slot][channel][column]
+#pragma unroll
+  for (int r = 0; r < 2; ++r)
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) w[r][c][j] = in[c * plane + size_t(gy[r]) * a.stride + gx[j]];
+#pragma unroll
+  for (int r = 0; r < kFinRows; ++r) {
+    if (r >= nrows) break;
+    const int u = r % 3, m = (r + 1) % 3, d = (r + 2) % 3;
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) w[d][c][j] = in[c * plane + size_t(gy[r + 2]) * a.stride + gx[j]];
+    float v[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const float e4 = (w[u][c][1] + w[m][c][0]) + (w[m][c][2] + w[d][c][1]);
+      const float cn = (w[u][c][0] + w[u][c][2]) + (w[d][c][0] + w[d][c][2]);
+      v[c] = fmaf(a.k0[c], w[m][c][1], fmaf(a.k1[c], e4, a.k2[c] * cn));
+    }
+    finish_store1(a, v, o0, o1, o2, ob + size_t(r) * a.out_stride, thr);
+  }
+}
+
+// One 64x32 tile; thread = one column of a kFinRows-row strip (x0 + tid % 64,
+// rows y0 + kFinRows (tid / 64) ..), so each row of a wave is one coalesced
+// load per channel and neighbour column.  Indices go through the 6.5
+// mirroring only in tiles that touch the frame edge.
+__device__ inline void finish_tile(const FinishArgs& a, int tbx, int tby) {
+  __shared__ float s_thr[257];
+  const int tid = threadIdx.x;
+  const int x0 = 64 * tbx, y0 = 32 * tby;
+  const float* thr = a.thr;
+  if (a.format == JXLR_OUT_U8_SRGB) {
+    for (int i = tid; i < 257; i += kFinThreads) s_thr[i] = a.thr[i];
+    __syncthreads();
+    thr = s_thr;
+  }
+  const int x = x0 + (tid & 63), ys = y0 + kFinRows * (tid >> 6);
+  if (x >= a.W || ys >= a.H) return;
+  const bool edge = x0 == 0 || x0 + 65 > a.W || y0 == 0 || y0 + 33 > a.H;
+  int gx[3], gy[kFinRows + 2];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) gx[j] = edge ? mirror(x - 1 + j, a.W) : x - 1 + j;
+#pragma unroll
+  for (int r = 0; r < kFinRows + 2; ++r) gy[r] = edge ? mirror(ys - 1 + r, a.H) : ys - 1 + r;
+  finish_strip(a, a.in, a.out[0], a.out[1], a.out[2], thr, x, gx, gy, ys,
+               min(kFinRows, a.H - ys));
 }
 
 // ---------------------------------------------------------------------------
@@ -874,7 +1067,7 @@ __global__ __launch_bounds__(kRecThreads) void recon_kernel(ReconArgs a) {
 __global__ __launch_bounds__(kThreads, 2) void epf_kernel(EpfArgs a) {
   epf_tile(a, blockIdx.x, blockIdx.y);
 }
-__global__ __launch_bounds__(kThreads) void finish_kernel(FinishArgs a) {
+__global__ __launch_bounds__(kFinThreads) void finish_kernel(FinishArgs a) {
   finish_tile(a, blockIdx.x, blockIdx.y);
 }
 
@@ -886,8 +1079,8 @@ static_assert(kRecTW == kEpfTW && kRecTH == kEpfTH && kRecTW == 64 && kRecTH == 
 struct FrameDesc {
   InfoArgs info;
   ReconArgs rec;
-  EpfArgs epf;     // in/out are set per pass
-  FinishArgs fin;  // in is set from the number of EPF passes
+  EpfArgs epf[2];  // even passes read xyb[0] and write xyb[1]; odd passes the reverse
+  FinishArgs fin;  // reads the XYB buffer the last EPF pass wrote
   float* xyb[2];
   int epf_iters;
   int tiles_x;     // 64x32 tiles per row
@@ -895,6 +1088,7 @@ struct FrameDesc {
 
 struct BatchArgs {
   const FrameDesc* __restrict__ frames;
+  const int* __restrict__ tile_frame;    // frame of each 64x32 tile
   const int* __restrict__ tile_start;    // n + 1 prefix offsets of 64x32 tiles
   const int* __restrict__ region_start;  // n + 1 prefix offsets of 32x32 regions
   int n;
@@ -942,38 +1136,36 @@ __global__ __launch_bounds__(kThreads) void blockinfo_batch_kernel(BatchArgs b) 
   }
 }
 
+// The batch kernels read each tile's frame arguments in place (uniform
+// addresses, so scalar loads), not as a private copy.
 __global__ __launch_bounds__(kRecThreads) void recon_batch_kernel(BatchArgs b) {
   for (TileRange r(b.order, b.tile_start[b.n]); r.t < r.end; r.t += r.step) {
     __syncthreads();
-    const int f = find_frame(b.tile_start, b.n, r.t);
-    const FrameDesc& d = b.frames[f];
-    const int lt = r.t - b.tile_start[f];
-    recon_tile(d.rec, lt % d.tiles_x, lt / d.tiles_x);
+    const int f = __builtin_amdgcn_readfirstlane(b.tile_frame[r.t]);  // uniform: scalar loads of d
+    const FrameDesc* __restrict__ d = b.frames + f;
+    const int lt = __builtin_amdgcn_readfirstlane(r.t - b.tile_start[f]);
+    recon_tile(d->rec, lt % d->tiles_x, lt / d->tiles_x);
   }
 }
 
 __global__ __launch_bounds__(kThreads, 2) void epf_batch_kernel(BatchArgs b) {
   for (TileRange r(b.order, b.tile_start[b.n]); r.t < r.end; r.t += r.step) {
     __syncthreads();
-    const int f = find_frame(b.tile_start, b.n, r.t);
-    const FrameDesc& d = b.frames[f];
-    if (b.pass >= d.epf_iters) continue;  // uniform over the workgroup
-    EpfArgs a = d.epf;
-    a.in = d.xyb[b.pass & 1];
-    a.out = d.xyb[(b.pass + 1) & 1];
-    const int lt = r.t - b.tile_start[f];
-    epf_tile(a, lt % d.tiles_x, lt / d.tiles_x);
+    const int f = __builtin_amdgcn_readfirstlane(b.tile_frame[r.t]);  // uniform: scalar loads of d
+    const FrameDesc* __restrict__ d = b.frames + f;
+    if (b.pass >= d->epf_iters) continue;  // uniform over the workgroup
+    const int lt = __builtin_amdgcn_readfirstlane(r.t - b.tile_start[f]);
+    epf_tile(d->epf[b.pass & 1], lt % d->tiles_x, lt / d->tiles_x);
   }
 }
 
-__global__ __launch_bounds__(kThreads) void finish_batch_kernel(BatchArgs b) {
+__global__ __launch_bounds__(kFinThreads) void finish_batch_kernel(BatchArgs b) {
   for (TileRange r(b.order, b.tile_start[b.n]); r.t < r.end; r.t += r.step) {
-    const int f = find_frame(b.tile_start, b.n, r.t);
-    const FrameDesc& d = b.frames[f];
-    FinishArgs a = d.fin;
-    a.in = d.xyb[d.epf_iters & 1];
-    const int lt = r.t - b.tile_start[f];
-    finish_tile(a, lt % d.tiles_x, lt / d.tiles_x);
+    __syncthreads();
+    const int f = __builtin_amdgcn_readfirstlane(b.tile_frame[r.t]);  // uniform: scalar loads of d
+    const FrameDesc* __restrict__ d = b.frames + f;
+    const int lt = __builtin_amdgcn_readfirstlane(r.t - b.tile_start[f]);
+    finish_tile(d->fin, lt % d->tiles_x, lt / d->tiles_x);
   }
 }
 
@@ -1005,6 +1197,7 @@ jxlr_status check_params(const jxlr_frame_params* p) {
   if (p->epf_sigma_shift < 0 || p->epf_sigma_shift > 8) return JXLR_E_PARAM;
   if (p->target_nits_div50 < 1) return JXLR_E_PARAM;
   if (p->out_format < JXLR_OUT_F32 || p->out_format > JXLR_OUT_U16_SRGB) return JXLR_E_PARAM;
+  if (p->idct_split < 0 || p->idct_split > 1) return JXLR_E_PARAM;
   return JXLR_OK;
 }
 
@@ -1211,6 +1404,14 @@ jxlr_status make_recon_args(jxlr_ctx* ctx, const jxlr_frame_params* p, const jxl
   a.xyb_stride = xyb_stride;
   a.status = ctx->status;
   a.tab = ctx->tables;
+  a.split = p->idct_split;
+  {
+    bool av = (io->ac_stride & 3) == 0;
+    for (int c = 0; c < 3; ++c) av = av && (reinterpret_cast<uintptr_t>(io->ac[c]) & 15) == 0;
+    a.ac_vec = av;
+    a.xyb_vec = (xyb_stride & 3) == 0 && (size_t(p->ysize) * xyb_stride & 3) == 0 &&
+                (reinterpret_cast<uintptr_t>(xyb) & 15) == 0;
+  }
   *out = a;
   return JXLR_OK;
 }
@@ -1353,7 +1554,7 @@ jxlr_status jxlr_finish(jxlr_ctx* ctx, const jxlr_frame_params* p, const jxlr_fr
   if (st) return st;
   DeviceGuard g(ctx->device);
   if (!g.ok) return JXLR_E_HIP;
-  hipLaunchKernelGGL(finish_kernel, dim3(tiles_x(p), tiles_y(p)), dim3(kThreads), 0, stream, a);
+  hipLaunchKernelGGL(finish_kernel, dim3(tiles_x(p), tiles_y(p)), dim3(kFinThreads), 0, stream, a);
   return launch_status(hipGetLastError());
 }
 
@@ -1385,14 +1586,17 @@ jxlr_status jxlr_decode(jxlr_ctx* ctx, const jxlr_frame_params* p, const jxlr_fr
 
 namespace {
 struct BatchLayout {
-  size_t frames, tile_start, region_start, header, total;
+  size_t frames, tile_frame, tile_start, region_start, header, total;
   std::vector<size_t> frame_off;  // per frame: info, then XYB buffers
 };
 
 BatchLayout batch_layout(int n, const jxlr_frame_params* p) {
   BatchLayout L;
+  size_t tiles = 0;
+  for (int i = 0; i < n; ++i) tiles += size_t(tiles_x(&p[i])) * tiles_y(&p[i]);
   L.frames = 0;
-  L.tile_start = round256(sizeof(FrameDesc) * size_t(n));
+  L.tile_frame = round256(sizeof(FrameDesc) * size_t(n));
+  L.tile_start = L.tile_frame + round256(sizeof(int) * tiles);
   L.region_start = L.tile_start + round256(sizeof(int) * size_t(n + 1));
   L.header = L.region_start + round256(sizeof(int) * size_t(n + 1));
   size_t off = L.header;
@@ -1421,6 +1625,7 @@ jxlr_status launch_stage(jxlr_ctx* ctx, const jxlr_batch_plan* plan, int stage, 
   char* base = static_cast<char*>(plan->ws);
   BatchArgs b;
   b.frames = reinterpret_cast<const FrameDesc*>(base + plan->frames_offset);
+  b.tile_frame = reinterpret_cast<const int*>(base + plan->tile_frame_offset);
   b.tile_start = reinterpret_cast<const int*>(base + plan->tile_start_offset);
   b.region_start = reinterpret_cast<const int*>(base + plan->region_start_offset);
   b.n = plan->n;
@@ -1442,7 +1647,7 @@ jxlr_status launch_stage(jxlr_ctx* ctx, const jxlr_batch_plan* plan, int stage, 
       hipLaunchKernelGGL(epf_batch_kernel, dim3(gsz), dim3(kThreads), 0, stream, b);
       break;
     case JXLR_STAGE_FINISH:
-      hipLaunchKernelGGL(finish_batch_kernel, dim3(gsz), dim3(kThreads), 0, stream, b);
+      hipLaunchKernelGGL(finish_batch_kernel, dim3(gsz), dim3(kFinThreads), 0, stream, b);
       break;
     default:
       return JXLR_E_PARAM;
@@ -1473,7 +1678,7 @@ jxlr_status jxlr_batch_prepare(jxlr_ctx* ctx, int n, const jxlr_frame_params* p,
   if (ws_bytes < L.total) return JXLR_E_WORKSPACE;
   char* base = static_cast<char*>(ws);
   std::vector<FrameDesc> frames(n);
-  std::vector<int> tstart(n + 1, 0), rstart(n + 1, 0);
+  std::vector<int> tstart(n + 1, 0), rstart(n + 1, 0), tframe;
   int max_epf = 0;
   for (int i = 0; i < n; ++i) {
     FrameDesc& d = frames[i];
@@ -1487,12 +1692,19 @@ jxlr_status jxlr_batch_prepare(jxlr_ctx* ctx, int n, const jxlr_frame_params* p,
     if (!st) st = make_recon_args(ctx, &p[i], &io[i], info, d.xyb[0], stride, &d.rec);
     if (!st && p[i].epf_iters > 0)
       st = make_epf_args(ctx, &p[i], &io[i], info, d.xyb[0], d.xyb[1], stride, nullptr, nullptr,
-                         &d.epf);
-    if (!st) st = make_finish_args(ctx, &p[i], &io[i], d.xyb[0], stride, &d.fin);
+                         &d.epf[0]);
+    if (!st && p[i].epf_iters > 1)
+      st = make_epf_args(ctx, &p[i], &io[i], info, d.xyb[1], d.xyb[0], stride, nullptr, nullptr,
+                         &d.epf[1]);
+    if (!st)
+      st = make_finish_args(ctx, &p[i], &io[i], d.xyb[p[i].epf_iters & 1], stride, &d.fin);
     if (st) return st;
     d.epf_iters = p[i].epf_iters;
     d.tiles_x = tiles_x(&p[i]);
-    tstart[i + 1] = tstart[i] + tiles_x(&p[i]) * tiles_y(&p[i]);
+    const long long nt = (long long)tstart[i] + tiles_x(&p[i]) * tiles_y(&p[i]);
+    if (nt > INT32_MAX / 2) return JXLR_E_SIZE;
+    tstart[i + 1] = int(nt);
+    tframe.resize(tstart[i + 1], i);
     rstart[i + 1] = rstart[i] + regions_of(&p[i]);
     max_epf = std::max(max_epf, p[i].epf_iters);
   }
@@ -1500,6 +1712,9 @@ jxlr_status jxlr_batch_prepare(jxlr_ctx* ctx, int n, const jxlr_frame_params* p,
   if (!g.ok) return JXLR_E_HIP;
   hipError_t e = hipMemcpy(base + L.frames, frames.data(), sizeof(FrameDesc) * n,
                            hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(base + L.tile_frame, tframe.data(), sizeof(int) * tframe.size(),
+                  hipMemcpyHostToDevice);
   if (e == hipSuccess)
     e = hipMemcpy(base + L.tile_start, tstart.data(), sizeof(int) * (n + 1), hipMemcpyHostToDevice);
   if (e == hipSuccess)
@@ -1513,6 +1728,7 @@ jxlr_status jxlr_batch_prepare(jxlr_ctx* ctx, int n, const jxlr_frame_params* p,
   plan->total_regions = rstart[n];
   plan->max_epf_iters = max_epf;
   plan->frames_offset = L.frames;
+  plan->tile_frame_offset = L.tile_frame;
   plan->tile_start_offset = L.tile_start;
   plan->region_start_offset = L.region_start;
   return JXLR_OK;
@@ -1571,7 +1787,7 @@ jxlr_status jxlr_autotune(jxlr_ctx* ctx, const jxlr_batch_plan* plan, int reps,
   const void* kerns[3] = {reinterpret_cast<const void*>(recon_batch_kernel),
                           reinterpret_cast<const void*>(epf_batch_kernel),
                           reinterpret_cast<const void*>(finish_batch_kernel)};
-  const int threads[3] = {kRecThreads, kThreads, kThreads};
+  const int threads[3] = {kRecThreads, kThreads, kFinThreads};
   jxlr_launch_config out{};
   float total_ms = 0.0f;
   for (int si = 0; si < 3 && !st; ++si) {

@@ -283,6 +283,38 @@ void srgb_thresholds(int bits, float* thr) {
   }
 }
 
+uint16_t bf16_rne(float v) {
+  uint32_t u;
+  std::memcpy(&u, &v, 4);
+  return uint16_t((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
+
+namespace {
+float bf16_value(uint16_t h) {
+  const uint32_t u = uint32_t(h) << 16;
+  float v;
+  std::memcpy(&v, &u, 4);
+  return v;
+}
+
+void build_mfma_operands(DeviceTables* t) {
+  const double pi = 3.14159265358979323846;
+  for (int m = 0; m < 3; ++m) {
+    const int N = 8 << m;
+    for (int step = 0; step < 2; ++step)
+      for (int l = 0; l < 64; ++l)
+        for (int e = 0; e < 8; ++e) {
+          const int i = l % 32, k = 16 * step + 8 * (l / 32) + e;
+          const double a = i / N == k / N ? std::cos(pi * (2 * (i % N) + 1) * (k % N) / (2.0 * N)) : 0.0;
+          const uint16_t hi = bf16_rne(float(a));
+          const uint16_t lo = bf16_rne(float(a - double(bf16_value(hi))));
+          t->mfma_a[m][0][step][l][e] = hi;
+          t->mfma_a[m][1][step][l][e] = lo;
+        }
+  }
+}
+}  // namespace
+
 bool build_tables(DeviceTables* t) {
   std::memset(t, 0, sizeof(*t));
   std::vector<double> m(32 * 32);
@@ -309,6 +341,7 @@ bool build_tables(DeviceTables* t) {
         as[x * n + i] = float(v * transform_scale(8 * n, x));
       }
   }
+  build_mfma_operands(t);
   srgb_thresholds(8, t->srgb_thr8);
   srgb_thresholds(16, t->srgb_thr16);
   std::vector<double> dq(1024);

@@ -61,6 +61,14 @@ struct DeviceTables {
   // c with srgb_thrB[c] <= v < srgb_thrB[c + 1].
   float srgb_thr8[257];
   float srgb_thr16[65537];
+  // Split-precision transform operands: the plain DCT-III matrix of a
+  // 32-sample region side made of 32 / N diagonal N-point blocks (m = 0, 1, 2
+  // for N = 8, 16, 32), A[i][k] = cos(pi (2 (i mod N) + 1)(k mod N) / (2 N))
+  // when i / N == k / N, else 0, as bfloat16 bit patterns of its high part
+  // (part 0, A rounded to nearest even) and of the rest (part 1), in the
+  // A-operand order of a 32x32x16 matrix instruction: element e of lane l in
+  // k-step t is A[l mod 32][16 t + 8 (l / 32) + e].
+  alignas(16) uint16_t mfma_a[3][2][2][64][8];
 };
 
 // Fills t on the host.  Returns false if a dequantization matrix entry is not
@@ -78,5 +86,7 @@ void epf_mul_table(int sigma_shift, int32_t* table);
 int srgb_code_f64(int bits, float v);
 // Fills thr[0 .. 2^bits] as described for DeviceTables::srgb_thr8/16.
 void srgb_thresholds(int bits, float* thr);
+// bfloat16 bit pattern of v rounded to nearest, ties to even.
+uint16_t bf16_rne(float v);
 
 }  // namespace jxlr

@@ -39,6 +39,7 @@ class FrameParams(C.Structure):
         ("opsin_bias", C.c_float * 3),
         ("target_nits_div50", C.c_int32),
         ("out_format", C.c_int32),
+        ("idct_split", C.c_int32),
     ]
 
 
@@ -58,7 +59,8 @@ class BatchPlan(C.Structure):
         ("ws", C.c_void_p), ("ws_bytes", C.c_size_t),
         ("n", C.c_int), ("total_tiles", C.c_int), ("total_regions", C.c_int),
         ("max_epf_iters", C.c_int),
-        ("frames_offset", C.c_size_t), ("tile_start_offset", C.c_size_t),
+        ("frames_offset", C.c_size_t), ("tile_frame_offset", C.c_size_t),
+        ("tile_start_offset", C.c_size_t),
         ("region_start_offset", C.c_size_t),
     ]
 

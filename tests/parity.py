@@ -96,7 +96,21 @@ def compare_rgb(p, gpu, orc):
     return dict(max_err=float(err[:, ok].max()) if ok.any() else 0.0,
                 max_err_affected=float(err[:, mask].max()) if mask.any() else 0.0,
                 affected=int(mask.sum()), pixels=int(mask.size), passes=stats,
-                max_abs_ref=float(np.abs(orc["rgb"]).max()))
+                max_abs_ref=float(np.abs(orc["rgb"]).max()), mask=mask)
+
+
+def max_err_by_type(frame, gpu, orc, mask):
+    """Max-abs RGB error over the pixels of each transform type's varblocks,
+    outside the flip-affected mask; keys are type numbers."""
+    H, W = mask.shape
+    types = np.kron(frame["strategy"], np.ones((8, 8), np.uint8))[:H, :W]
+    e = np.abs(gpu["out"].astype(np.float64) - orc["rgb"]).max(axis=0)
+    res = {}
+    for t in np.unique(types):
+        sel = (types == t) & ~mask
+        if sel.any():
+            res[int(t)] = float(e[sel].max())
+    return res
 
 
 def srgb_codes_check(p, codes, orc, gpu_epf, bits):

@@ -40,7 +40,7 @@ def test_defaults_agree_with_oracle():
     p = J.params(64, 48)
     q = O.params(64, 48)
     for name, _ in J.FrameParams._fields_:
-        if name == "out_format":
+        if name in ("out_format", "idct_split"):
             continue
         a, b = getattr(p, name), getattr(q, name)
         if isinstance(a, C.Array):
@@ -79,6 +79,7 @@ def test_validate_maps_host():
 def test_parameter_ranges():
     f = _frame()
     for k, v in [("epf_weight_min", 1.5), ("epf_sigma_max", 700), ("epf_sigma_shift", 9),
+                 ("idct_split", 2), ("idct_split", -1),
                  ("epf_iters", 4), ("global_scale", 0), ("target_nits_div50", 0),
                  ("out_format", 3)]:
         p = J.params(64, 64, **{k: v})
@@ -124,6 +125,7 @@ def shim(tmp_path_factory):
         getattr(L, f).restype = C.POINTER(C.c_float)
     L.shim_mul.restype = C.POINTER(C.c_int32)
     L.shim_thr.restype = C.POINTER(C.c_float)
+    L.shim_mfma.restype = C.POINTER(C.c_uint16)
     assert L.shim_build() == 1
     return L
 
@@ -236,3 +238,25 @@ def test_srgb_thresholds_match_oracle_rounding(shim, bits):
     assert np.all(np.diff(t) > 0)
     np.testing.assert_array_equal(O.quantize_srgb(bits, t.astype(np.float64)), k)
     np.testing.assert_array_equal(O.quantize_srgb(bits, below.astype(np.float64)), k - 1)
+
+
+@pytest.mark.parametrize("m", [0, 1, 2])
+def test_split_transform_operands(shim, m):
+    # the split matrices, put back in matrix order, are the block-diagonal
+    # plain DCT-III of 8 << m points; hi is the bfloat16 rounding of each
+    # entry and hi + lo is within 2^-17 of it
+    raw = np.ctypeslib.as_array(shim.shim_mfma(m), shape=(2 * 2 * 64 * 8,)).copy()
+    parts = (raw.astype(np.uint32) << 16).view(np.float32).reshape(2, 2, 64, 8).astype(np.float64)
+    A = np.zeros((2, 32, 32))
+    for part in range(2):
+        for step in range(2):
+            for lane in range(64):
+                for e in range(8):
+                    A[part, lane % 32, 16 * step + 8 * (lane // 32) + e] = parts[part, step, lane, e]
+    N = 8 << m
+    i, k = np.meshgrid(np.arange(32), np.arange(32), indexing="ij")
+    ref = np.where(i // N == k // N, np.cos(np.pi * (2 * (i % N) + 1) * (k % N) / (2 * N)), 0.0)
+    assert np.abs(A[0] + A[1] - ref).max() <= 2.0 ** -17
+    hi_bits = raw.reshape(2, 2, 64, 8)[0]
+    assert np.all(np.abs(A[0] - ref) <= np.abs(ref) * 2.0 ** -8 + 1e-30)
+    assert hi_bits.dtype == np.uint16
