@@ -358,17 +358,101 @@ def bench_batch(args, J, wl, torch, np):
     }
 
 
+def bench_serving(args, J, wl, torch, np):
+    from paper_1908_03565_amd import serving
+    log("bench: generating the 4096x4096 source frame of the requests")
+    mother = wl.c5_mother()
+    reqs = wl.c5_requests(rate=args.c5_rate, seconds=args.c5_seconds)
+    arrivals = [(q[0], q[1:]) for q in reqs]
+    make = lambda q: wl.crop(mother, q[2], q[3], q[0], q[1], epf_iters=q[4], out_format=q[5])
+    ctx = J.Context(0)
+    budget = int(args.c5_budget_gb * 2**30)
+    # warm-up: a few requests through the same server path, not timed
+    serving.run(ctx, [(0.0, q) for _, q in arrivals[:8]], make, budget, split=int(args.split))
+    log(f"bench: serving {len(arrivals)} requests over {args.c5_seconds} s "
+        f"(Poisson {args.c5_rate}/s), budget {args.c5_budget_gb} GiB")
+    keep_every = max(1, len(arrivals) // 64)
+    srv, wall = serving.run(ctx, arrivals, make, budget, split=int(args.split),
+                            keep_every=keep_every)
+    summ = serving.summarize(srv, wall)
+    log(f"bench: {summ}")
+    assert ctx.device_status() == 0
+    err = cpu = None
+    if not args.no_check or not args.no_cpu_baseline:
+        from oracle import oracle as O
+        from tests import parity as P
+        kept = sorted((r for r in srv.done if r.keep), key=lambda r: r.params.xsize * r.params.ysize)
+        # every kept request (a uniform sample) equals its decode alone
+        for r in kept:
+            df = J.DeviceFrame(r.frame)
+            o = ctx.empty_out(r.params)
+            ctx.decode(r.params, df, o, ctx.workspace(r.params))
+            assert torch.equal(o.cpu(), r.host_out), f"request {r.rid} differs from its decode alone"
+        res = []
+        if not args.no_check:
+            for r in kept[:4]:
+                fr, p = r.frame, r.params
+                bits = 8 if p.out_format == 1 else 16
+                p32 = J.params(p.xsize, p.ysize, out_format=0, idct_split=p.idct_split, **fr["params"])
+                lin = ctx.empty_out(p32)
+                ctx.decode(p32, J.DeviceFrame(fr), lin, ctx.workspace(p32))
+                exact = bool(np.array_equal(O.quantize_srgb(bits, lin.cpu().numpy().astype(np.float64)),
+                                            r.host_out.numpy()))
+                orc = O.decode_stages(O.params(p.xsize, p.ysize, **fr["params"]), fr)
+                gpu = P.gpu_stages(ctx, p32, J.DeviceFrame(fr))
+                cmp = P.compare_rgb(p32, gpu, orc)
+                res.append(dict(request=r.rid, size=[p.xsize, p.ysize], epf_iters=p.epf_iters,
+                                bits=bits, codes_equal_rounding=exact, max_abs_err=cmp["max_err"],
+                                flip_affected_px=cmp["affected"]))
+                assert exact
+        err = dict(served_equals_alone=f"{len(kept)} sampled requests (every {keep_every}th)",
+                   oracle_sample=res)
+        if not args.no_cpu_baseline:
+            done_px, n_done, t = 0, 0, time.perf_counter()
+            for r in kept:
+                fr = r.frame
+                O.decode(O.params(fr["xsize"], fr["ysize"], **fr["params"]), fr)
+                done_px += fr["xsize"] * fr["ysize"]
+                n_done += 1
+                if time.perf_counter() - t > args.cpu_seconds:
+                    break
+            cpu_s = time.perf_counter() - t
+            cpu = dict(value=round(done_px / 1e6 / cpu_s, 4), unit="MP/s", cores=O.num_threads(),
+                       kind="oracle",
+                       sample=f"{n_done} sampled requests, smallest first, {done_px / 1e6:.2f} MP "
+                              f"in {cpu_s:.2f} s, FP64 scalar C, OpenMP")
+    return {
+        "value": summ["mp_per_s"],
+        "ms_per_step": round(wall * 1e3 / max(1, summ["requests"]), 5),
+        "dtype": "f32",
+        "config": {"workload": "c5_serving_poisson", "rate_per_s": args.c5_rate,
+                   "seconds": args.c5_seconds, "requests": summ["requests"],
+                   "megapixels": summ["megapixels"], "budget_gib": args.c5_budget_gb,
+                   "output": "70% u8 / 30% u16 sRGB", "epf_iters": "U{0..3}",
+                   "idct": "split bf16 hi+lo on matrix cores, f32 accumulate" if args.split
+                   else "f32"},
+        "latency_ms": summ["latency_ms"],
+        "serving": summ,
+        "error": err,
+        "roofline": None,
+        "cpu_baseline": cpu,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c1x1024"])
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c1x1024", "c5"])
     ap.add_argument("--no-check", action="store_true", help="skip the oracle comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="bound on the oracle's CPU time for the batch workloads")
     ap.add_argument("--retune", action="store_true", help="ignore cached batch schedules")
+    ap.add_argument("--c5-rate", type=float, default=200.0, help="serving: arrivals per second")
+    ap.add_argument("--c5-seconds", type=float, default=60.0, help="serving: arrival window")
+    ap.add_argument("--c5-budget-gb", type=float, default=8.0, help="serving: HBM budget (GiB)")
     ap.add_argument("--split", action="store_true",
                     help="split-precision (bf16 hi+lo matrix-core) inverse transform")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -397,7 +481,10 @@ def main():
         print(json.dumps({"copy_probe_bytes_read": n * 4, "copy_probe_bytes_written": n * 4,
                           "launches": 5}))
         return
-    run = bench_batch if args.workload in ("c4", "c1x1024") else bench_frame
+    if args.workload == "c5":
+        run = bench_serving
+    else:
+        run = bench_batch if args.workload in ("c4", "c1x1024") else bench_frame
     r = run(args, J, wl, torch, np)
     res = {"metric": METRIC, "value": r.pop("value"), "unit": "MP/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": r.pop("ms_per_step"),

@@ -17,6 +17,10 @@ JPEG XL codestreams; no codestream or image data is involved):
   c4      a batch of 64 frames, sides log-uniform in [256, 3072] rounded to 8,
           EPF 1 pass, 8-bit sRGB output, seed 4
   small   the c2 recipe at a size the oracle finishes in seconds
+  c5      serving requests: sides log-uniform in [64, 4096] rounded to 8, 30%
+          16-bit / 70% 8-bit sRGB output, EPF passes U{0..3}, cut at 64-pixel
+          aligned offsets out of one 4096x4096 frame of the c2 recipe (seed 5)
+          with Poisson arrivals at 200 per second (seed 5)
 """
 import math
 
@@ -42,6 +46,10 @@ MIXED = [DCT8, DCT4, DCT2, IDENTITY, DCT16, DCT32, DCT8X16, DCT16X8, DCT16X32, D
 # [-3.2, 3.2] on the [0,1] scale at 2048x2048).
 BASE_PARAMS = dict(global_scale=65536, dc_mul=(2.0 ** -14, 2.0 ** -10, 2.0 ** -10),
                    extra_levels=(0, 0, 0))
+
+
+_BX = np.array([BLOCKS[s][0] for s in range(len(BLOCKS))], np.int32)
+_BY = np.array([BLOCKS[s][1] for s in range(len(BLOCKS))], np.int32)
 
 
 def _fits(s, wb, hb):
@@ -175,3 +183,61 @@ def c4_sizes(seed=4, n=64):
 def c4(n=64, seed=4):
     return [frame(w, h, seed=seed * 1000 + i, epf_iters=1, gab=1, out_format=1,
                   name=f"c4_{i}_{w}x{h}") for i, (w, h) in enumerate(c4_sizes(seed, n))]
+
+
+def crop(mother, x0, y0, W, H, epf_iters=None, out_format=None, name=None):
+    """The W x H part of `mother` at pixel offset (x0, y0), both multiples of
+    64 (so the 32x32 regions and the 64x64 chroma-from-luma tiles stay
+    aligned), as a frame of its own.  Varblocks cut by the new right or bottom
+    edge become DCT8 blocks, so the DctSelect map stays well-formed."""
+    assert x0 % 64 == 0 and y0 % 64 == 0
+    assert x0 + W <= mother["xsize"] and y0 + H <= mother["ysize"]
+    bx0, by0 = x0 // 8, y0 // 8
+    Wb, Hb = (W + 7) // 8, (H + 7) // 8
+    smap = mother["strategy"][by0:by0 + Hb, bx0:bx0 + Wb].copy()
+    cx = _BX[smap]
+    cy = _BY[smap]
+    # a varblock's blocks sit at offsets (bx mod cx, by mod cy); it is cut when
+    # its last column or row falls outside
+    end_x = (np.arange(Wb)[None, :] // cx) * cx + cx
+    end_y = (np.arange(Hb)[:, None] // cy) * cy + cy
+    smap[(end_x > Wb) | (end_y > Hb)] = DCT8
+    params = dict(mother["params"])
+    if epf_iters is not None:
+        params["epf_iters"] = epf_iters
+    Wt, Ht = (W + 63) // 64, (H + 63) // 64
+    return dict(name=name or f"crop_{W}x{H}", xsize=W, ysize=H,
+                ac=np.ascontiguousarray(mother["ac"][:, 8 * by0:8 * (by0 + Hb), 8 * bx0:8 * (bx0 + Wb)]),
+                dc=np.ascontiguousarray(mother["dc"][:, by0:by0 + Hb, bx0:bx0 + Wb]),
+                strategy=smap,
+                qf=np.ascontiguousarray(mother["qf"][by0:by0 + Hb, bx0:bx0 + Wb]),
+                sharpness=np.ascontiguousarray(mother["sharpness"][by0:by0 + Hb, bx0:bx0 + Wb]),
+                cfl_kx=np.ascontiguousarray(mother["cfl_kx"][y0 // 64:y0 // 64 + Ht, x0 // 64:x0 // 64 + Wt]),
+                cfl_kb=np.ascontiguousarray(mother["cfl_kb"][y0 // 64:y0 // 64 + Ht, x0 // 64:x0 // 64 + Wt]),
+                params=params,
+                out_format=mother["out_format"] if out_format is None else out_format)
+
+
+def c5_mother():
+    return frame(4096, 4096, seed=5, epf_iters=2, gab=1, name="c5_mother_4096x4096")
+
+
+def c5_requests(rate=200.0, seconds=60.0, seed=5, lo=64, hi=4096):
+    """Arrival times (seconds, Poisson process) and per-request recipes:
+    (t, W, H, x0, y0, epf_iters, out_format)."""
+    rng = np.random.default_rng(seed)
+    reqs = []
+    t = 0.0
+    while True:
+        t += rng.exponential(1.0 / rate)
+        if t >= seconds:
+            break
+        w, h = np.exp(rng.uniform(math.log(lo), math.log(hi), size=2))
+        W = int(min(hi, max(lo, round(w / 8) * 8)))
+        H = int(min(hi, max(lo, round(h / 8) * 8)))
+        x0 = 64 * int(rng.integers(0, (4096 - W) // 64 + 1))
+        y0 = 64 * int(rng.integers(0, (4096 - H) // 64 + 1))
+        epf = int(rng.integers(0, 4))
+        fmt = 2 if rng.random() < 0.3 else 1
+        reqs.append((t, W, H, x0, y0, epf, fmt))
+    return reqs

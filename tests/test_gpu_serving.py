@@ -1,0 +1,67 @@
+"""GPU test of the continuous-batching server: requests of uneven sizes,
+EPF pass counts and output formats arrive in a burst under an HBM budget that
+holds only part of them; every result must be bit-identical to decoding that
+request alone, batches must hold several requests, and the admitted
+footprint must never exceed the budget."""
+import numpy as np
+import pytest
+
+from paper_1908_03565_amd import workload as wl
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_1908_03565_amd import jxlr as J
+    return J.Context(0)
+
+
+def _recipes(n, seed):
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n):
+        W = int(np.clip(round(np.exp(rng.uniform(np.log(64), np.log(512))) / 8) * 8, 64, 512))
+        H = int(np.clip(round(np.exp(rng.uniform(np.log(64), np.log(512))) / 8) * 8, 64, 512))
+        x0 = 64 * int(rng.integers(0, (1024 - W) // 64 + 1))
+        y0 = 64 * int(rng.integers(0, (1024 - H) // 64 + 1))
+        # bursts of six simultaneous arrivals, 5 ms apart
+        out.append((0.005 * (i // 6), (W, H, x0, y0, int(rng.integers(0, 4)), int(rng.integers(0, 3)))))
+    return out
+
+
+@pytest.mark.parametrize("split", [0, 1])
+def test_served_equals_alone(ctx, split):
+    import torch
+    from paper_1908_03565_amd import jxlr as J
+    from paper_1908_03565_amd import serving
+    mother = wl.frame(1024, 1024, seed=55, epf_iters=2)
+    arrivals = _recipes(24, 7 + split)
+    make = lambda q: wl.crop(mother, q[2], q[3], q[0], q[1], epf_iters=q[4], out_format=q[5])
+    fps = []
+    for _, q in arrivals:
+        fr = make(q)
+        fps.append(serving.footprint_bytes(J.params(fr["xsize"], fr["ysize"],
+                                                    out_format=fr["out_format"], **fr["params"])))
+    budget = int(0.35 * sum(fps))
+    assert budget >= max(fps)
+    srv, wall = serving.run(ctx, arrivals, make, budget, split=split, max_batch=8, keep_every=1)
+    assert len(srv.done) == len(arrivals)
+    assert srv.peak_used <= budget
+    assert srv.batches > 1 and max(srv.batch_sizes) > 1
+    assert ctx.device_status() == 0
+    for r in srv.done:
+        df = J.DeviceFrame(r.frame)
+        o = ctx.empty_out(r.params)
+        ctx.decode(r.params, df, o, ctx.workspace(r.params))
+        torch.cuda.synchronize()
+        assert torch.equal(o.cpu(), r.host_out), f"request {r.rid} {r.params.xsize}x{r.params.ysize}"
+    print(serving.summarize(srv, wall))
+
+
+def test_request_over_budget_is_refused(ctx):
+    from paper_1908_03565_amd import serving
+    mother = wl.frame(256, 256, seed=56, epf_iters=1)
+    make = lambda q: wl.crop(mother, 0, 0, 256, 256, epf_iters=1, out_format=1)
+    with pytest.raises(RuntimeError, match="over the budget"):
+        serving.run(ctx, [(0.0, None)], make, budget_bytes=1 << 20)

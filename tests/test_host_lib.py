@@ -260,3 +260,39 @@ def test_split_transform_operands(shim, m):
     hi_bits = raw.reshape(2, 2, 64, 8)[0]
     assert np.all(np.abs(A[0] - ref) <= np.abs(ref) * 2.0 ** -8 + 1e-30)
     assert hi_bits.dtype == np.uint16
+
+
+def test_crops_are_well_formed_frames():
+    mother = wl.frame(1024, 768, seed=57, epf_iters=2)
+    rng = np.random.default_rng(3)
+    for _ in range(40):
+        W = int(rng.integers(1, 129)) * 8
+        H = int(rng.integers(1, 97)) * 8
+        x0 = 64 * int(rng.integers(0, (1024 - W) // 64 + 1))
+        y0 = 64 * int(rng.integers(0, (768 - H) // 64 + 1))
+        f = wl.crop(mother, x0, y0, W, H, epf_iters=1, out_format=2)
+        p = J.params(W, H, out_format=f["out_format"], **f["params"])
+        assert J.validate_maps_host(p, f) == 0, (W, H, x0, y0)
+        # coefficients and DC are the mother's, position for position
+        np.testing.assert_array_equal(f["ac"][:, :8, :8], mother["ac"][:, y0:y0 + 8, x0:x0 + 8])
+        assert f["cfl_kx"].shape == ((H + 63) // 64, (W + 63) // 64)
+
+
+def test_serving_requests_recipe():
+    reqs = wl.c5_requests()
+    assert 11000 < len(reqs) < 13000          # Poisson 200/s over 60 s
+    t = np.array([q[0] for q in reqs])
+    assert np.all(np.diff(t) > 0) and t[-1] < 60.0
+    W = np.array([q[1] for q in reqs]); H = np.array([q[2] for q in reqs])
+    assert W.min() >= 64 and W.max() <= 4096 and np.all(W % 8 == 0) and np.all(H % 8 == 0)
+    u16 = np.mean([q[6] == 2 for q in reqs])
+    assert 0.27 < u16 < 0.33
+    assert set(q[5] for q in reqs) == {0, 1, 2, 3}
+    assert all(q[3] + q[1] <= 4096 and q[4] + q[2] <= 4096 and q[3] % 64 == 0 for q in reqs)
+
+
+def test_footprint_covers_workspace():
+    from paper_1908_03565_amd import serving
+    p = J.params(640, 480, epf_iters=2, out_format=2)
+    fp = serving.footprint_bytes(p)
+    assert fp >= J.workspace_bytes(p) + 640 * 480 * 12 + 3 * 640 * 480 * 2  # AC in, u16 out
