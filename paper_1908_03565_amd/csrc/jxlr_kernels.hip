@@ -1,14 +1,19 @@
 // HIP kernels of the VarDCT reconstruction library for CDNA4 (gfx950), and
 // the C-ABI entry points that launch them.
 //
-// Kernels (all 256 threads = 4 wave64 per workgroup):
-//   recon_kernel   one workgroup per 32x32-pixel region: F.2/F.3 dequant,
-//                  Annex G chroma from luma, I.2.7 LLF from DC and the I.2.4
-//                  inverse transforms, staged in LDS; writes XYB planes.
-//   epf_kernel     one workgroup per 32x32 output tile: one J.2 pass with the
-//                  tile and its filter halo staged in LDS.
-//   finish_kernel  one thread per pixel: J.4 Gaborish and L.2 XYB -> RGB,
-//                  optional sRGB 8/16-bit encoding.
+// Kernels (every stage works on 64x32-pixel tiles, two 32x32 regions):
+//   blockinfo_kernel  one thread per 32x32 region: the C.5.4 raster scan of
+//                     DctSelect, one info byte per 8x8 block.
+//   recon_kernel      192 threads per tile: F.2/F.3 dequant, Annex G chroma
+//                     from luma, I.2.7 LLF from DC and the I.2.4 inverse
+//                     transforms (binary32 passes, or split-precision matrix-
+//                     core products), staged in LDS; writes XYB planes.
+//   epf_kernel        256 threads per tile: one J.2 pass with the tile and
+//                     its filter halo staged in LDS.
+//   finish_kernel     512 threads per tile: J.4 Gaborish and L.2 XYB -> RGB,
+//                     sRGB 8/16-bit codes exact to the binary64 definition.
+// The *_batch_kernel variants run the same tile bodies over the tile list of
+// many frames with a persistent, tunable grid.
 // Varblocks are naturally aligned and at most 32x32 (C.5.4), so every
 // varblock lies inside exactly one 32x32 region; the region is the unit of
 // work of the reconstruction and of the EPF sigma computation.

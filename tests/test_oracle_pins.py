@@ -713,3 +713,28 @@ def test_quantize_codes_at_rounding_boundaries(bits):
     np.testing.assert_array_equal(below, k - 1)
     ends = O.quantize_srgb(bits, np.array([-0.5, 0.0, 1.0, 3.0]))
     np.testing.assert_array_equal(ends, [0, 0, maxv, maxv])
+
+
+def _golden_defaults():
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "draft_defaults.txt")
+    vals = {}
+    for line in open(path):
+        line = line.strip()
+        if line and not line.startswith("#"):
+            name, *nums = line.split()
+            vals[name] = [float(v) for v in nums]
+    return vals
+
+
+def test_defaults_match_draft_golden():
+    # the defaults both sides start from are the values the draft prints
+    # (C.10 loop filter, L.2 opsin matrix and biases, C.4.3 / Annex G factors);
+    # binary32 storage allows a relative 6e-8
+    from paper_1908_03565_amd import jxlr as J
+    gold = _golden_defaults()
+    for side, p in (("oracle", O.params(64, 64)), ("library", J.params(64, 64))):
+        for name, want in gold.items():
+            got = getattr(p, name)
+            got = list(got) if hasattr(got, "__len__") else [got]
+            np.testing.assert_allclose(got, want, rtol=6e-8, atol=0, err_msg=f"{side} {name}")
