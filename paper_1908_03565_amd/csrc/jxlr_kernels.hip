@@ -397,7 +397,7 @@ static_assert(offsetof(DeviceTables, dqs) % 16 == 0, "16-byte loads of dequantiz
 constexpr int kRecGPT = (kRecGroups + kRecThreads - 1) / kRecThreads;
 
 // One 64x32 tile (tile column tbx, row tby) of the reconstruction.
-__device__ inline void recon_tile(const ReconArgs& a, int tbx, int tby) {
+__device__ __attribute__((always_inline)) inline void recon_tile(const ReconArgs& a, int tbx, int tby) {
   __shared__ float coef[3][kRecTH][kRecLd];
   // DC samples per tile block (b = row * 8 + column), zero-padded so that a
   // fixed 4x4 window starting at any block stays inside the array.
@@ -710,7 +710,7 @@ __device__ inline uint32_t guide_byte(float v, float minv, float scale) {
 
 // One 64x32 output tile of an EPF pass.  Threads may return after the last
 // barrier.
-__device__ inline void epf_tile(const EpfArgs& a, int tbx, int tby) {
+__device__ __attribute__((always_inline)) inline void epf_tile(const EpfArgs& a, int tbx, int tby) {
   __shared__ float s_in[3][kInH][kInW];
   __shared__ uint32_t s_p[3][kPH][kPW];
   __shared__ uint32_t s_w[3][kPH][kGW + 1];
@@ -797,6 +797,7 @@ __device__ inline void epf_tile(const EpfArgs& a, int tbx, int tby) {
     if (gy < a.H)
       for (int j = 0; j < 8; ++j) {
         if (x0 + 8 * bxl + j >= a.W) break;
+#pragma unroll
         for (int c = 0; c < 3; ++c) {
           const float sc = (s_in[c][3 + 8 * byl + r][3 + 8 * bxl + j] - a.minv[c]) * a.scale[c];
           lo[c] = fminf(lo[c], sc);
@@ -804,6 +805,7 @@ __device__ inline void epf_tile(const EpfArgs& a, int tbx, int tby) {
         }
       }
     float rg = 0.0f;
+#pragma unroll
     for (int c = 0; c < 3; ++c) {
       for (int m = 1; m < 8; m <<= 1) {
         lo[c] = fminf(lo[c], __shfl_xor(lo[c], m, 8));
@@ -826,7 +828,13 @@ __device__ inline void epf_tile(const EpfArgs& a, int tbx, int tby) {
       for (int m = 0; m < 16; ++m)
         if (s_owner[r][m] == s_owner[r][lb]) rg = fmaxf(rg, s_rng[(m >> 2) * 8 + 4 * r + (m & 3)]);
       const size_t mi = size_t(by) * a.map_stride + bx;
-      float sg = fminf(rg, a.range_max) * a.range_mul * a.sharp_lut[a.sharp[mi] & 7];
+      // sharp_lut[sharpness] as a select chain (no dynamic index into the
+      // arguments, which may live in registers)
+      const int sh = a.sharp[mi] & 7;
+      float lut = a.sharp_lut[0];
+#pragma unroll
+      for (int i = 1; i < 8; ++i) lut = sh == i ? a.sharp_lut[i] : lut;
+      float sg = fminf(rg, a.range_max) * a.range_mul * lut;
       sg = fminf(sg, a.gscale_q * float(1 + a.qf[mi]) * a.quant_mul);
       sg = fminf(sg, a.sigma_max);
       sig = int(sg);  // truncation; sg >= 0
@@ -1034,7 +1042,7 @@ __device__ inline void finish_strip(const FinishArgs& a, const float* __restrict
 // rows y0 + kFinRows (tid / 64) ..), so each row of a wave is one coalesced
 // load per channel and neighbour column.  Indices go through the 6.5
 // mirroring only in tiles that touch the frame edge.
-__device__ inline void finish_tile(const FinishArgs& a, int tbx, int tby) {
+__device__ __attribute__((always_inline)) inline void finish_tile(const FinishArgs& a, int tbx, int tby) {
   __shared__ float s_thr[257];
   const int tid = threadIdx.x;
   const int x0 = 64 * tbx, y0 = 32 * tby;
@@ -1141,36 +1149,68 @@ __global__ __launch_bounds__(kThreads) void blockinfo_batch_kernel(BatchArgs b) 
   }
 }
 
-// The batch kernels read each tile's frame arguments in place (uniform
-// addresses, so scalar loads), not as a private copy.
+// The batch kernels copy each tile's frame arguments out of the descriptor
+// table through a constant-address-space pointer: the table is not written
+// while a batch runs, so the copy is made with scalar loads and the arguments
+// live in scalar registers, as kernel arguments do.
+template <typename T>
+__device__ inline T const_load(const T* p) {
+  T v;
+  __builtin_memcpy(&v, (const __attribute__((address_space(4))) void*)(uintptr_t)(p), sizeof(T));
+  return v;
+}
+
+// PERSIST: the workgroup walks tiles (TileRange); otherwise it takes tile
+// blockIdx.x only, which keeps the register allocation of the single-frame
+// kernels.
+template <bool PERSIST>
 __global__ __launch_bounds__(kRecThreads) void recon_batch_kernel(BatchArgs b) {
   for (TileRange r(b.order, b.tile_start[b.n]); r.t < r.end; r.t += r.step) {
-    __syncthreads();
-    const int f = __builtin_amdgcn_readfirstlane(b.tile_frame[r.t]);  // uniform: scalar loads of d
-    const FrameDesc* __restrict__ d = b.frames + f;
+    if (PERSIST) __syncthreads();
+    const int f = __builtin_amdgcn_readfirstlane(b.tile_frame[r.t]);
+    const FrameDesc* d = b.frames + f;
     const int lt = __builtin_amdgcn_readfirstlane(r.t - b.tile_start[f]);
-    recon_tile(d->rec, lt % d->tiles_x, lt / d->tiles_x);
+    const int tx = const_load(&d->tiles_x);
+    const ReconArgs a = const_load(&d->rec);
+    recon_tile(a, lt % tx, lt / tx);
+    if (!PERSIST) break;
   }
 }
 
+template <bool PERSIST>
 __global__ __launch_bounds__(kThreads, 2) void epf_batch_kernel(BatchArgs b) {
   for (TileRange r(b.order, b.tile_start[b.n]); r.t < r.end; r.t += r.step) {
-    __syncthreads();
-    const int f = __builtin_amdgcn_readfirstlane(b.tile_frame[r.t]);  // uniform: scalar loads of d
-    const FrameDesc* __restrict__ d = b.frames + f;
-    if (b.pass >= d->epf_iters) continue;  // uniform over the workgroup
-    const int lt = __builtin_amdgcn_readfirstlane(r.t - b.tile_start[f]);
-    epf_tile(d->epf[b.pass & 1], lt % d->tiles_x, lt / d->tiles_x);
+    if (PERSIST) __syncthreads();
+    const int f = __builtin_amdgcn_readfirstlane(b.tile_frame[r.t]);
+    const FrameDesc* d = b.frames + f;
+    if (b.pass < const_load(&d->epf_iters)) {  // uniform over the workgroup
+      const int lt = __builtin_amdgcn_readfirstlane(r.t - b.tile_start[f]);
+      const int tx = const_load(&d->tiles_x);
+      // the pass's arguments are staged in LDS (a private copy of this
+      // structure would be kept in scratch memory)
+      __shared__ EpfArgs s_args;
+      static_assert(sizeof(EpfArgs) % 4 == 0, "word copy");
+      if (threadIdx.x < sizeof(EpfArgs) / 4)
+        reinterpret_cast<uint32_t*>(&s_args)[threadIdx.x] =
+            reinterpret_cast<const uint32_t*>(&d->epf[b.pass & 1])[threadIdx.x];
+      __syncthreads();
+      epf_tile(s_args, lt % tx, lt / tx);
+    }
+    if (!PERSIST) break;
   }
 }
 
+template <bool PERSIST>
 __global__ __launch_bounds__(kFinThreads) void finish_batch_kernel(BatchArgs b) {
   for (TileRange r(b.order, b.tile_start[b.n]); r.t < r.end; r.t += r.step) {
-    __syncthreads();
-    const int f = __builtin_amdgcn_readfirstlane(b.tile_frame[r.t]);  // uniform: scalar loads of d
-    const FrameDesc* __restrict__ d = b.frames + f;
+    if (PERSIST) __syncthreads();
+    const int f = __builtin_amdgcn_readfirstlane(b.tile_frame[r.t]);
+    const FrameDesc* d = b.frames + f;
     const int lt = __builtin_amdgcn_readfirstlane(r.t - b.tile_start[f]);
-    finish_tile(d->fin, lt % d->tiles_x, lt / d->tiles_x);
+    const int tx = const_load(&d->tiles_x);
+    const FinishArgs a = const_load(&d->fin);
+    finish_tile(a, lt % tx, lt / tx);
+    if (!PERSIST) break;
   }
 }
 
@@ -1641,18 +1681,28 @@ jxlr_status launch_stage(jxlr_ctx* ctx, const jxlr_batch_plan* plan, int stage, 
   b.order = order == 1 && gsz >= 8 ? 1 : 0;
   if (b.order) gsz &= ~7;
   (void)ctx;
+  const bool persist = gsz < full;
   switch (stage) {
     case JXLR_STAGE_INFO:
       hipLaunchKernelGGL(blockinfo_batch_kernel, dim3(gsz), dim3(kThreads), 0, stream, b);
       break;
     case JXLR_STAGE_RECON:
-      hipLaunchKernelGGL(recon_batch_kernel, dim3(gsz), dim3(kRecThreads), 0, stream, b);
+      if (persist)
+        hipLaunchKernelGGL(recon_batch_kernel<true>, dim3(gsz), dim3(kRecThreads), 0, stream, b);
+      else
+        hipLaunchKernelGGL(recon_batch_kernel<false>, dim3(gsz), dim3(kRecThreads), 0, stream, b);
       break;
     case JXLR_STAGE_EPF:
-      hipLaunchKernelGGL(epf_batch_kernel, dim3(gsz), dim3(kThreads), 0, stream, b);
+      if (persist)
+        hipLaunchKernelGGL(epf_batch_kernel<true>, dim3(gsz), dim3(kThreads), 0, stream, b);
+      else
+        hipLaunchKernelGGL(epf_batch_kernel<false>, dim3(gsz), dim3(kThreads), 0, stream, b);
       break;
     case JXLR_STAGE_FINISH:
-      hipLaunchKernelGGL(finish_batch_kernel, dim3(gsz), dim3(kFinThreads), 0, stream, b);
+      if (persist)
+        hipLaunchKernelGGL(finish_batch_kernel<true>, dim3(gsz), dim3(kFinThreads), 0, stream, b);
+      else
+        hipLaunchKernelGGL(finish_batch_kernel<false>, dim3(gsz), dim3(kFinThreads), 0, stream, b);
       break;
     default:
       return JXLR_E_PARAM;
@@ -1789,9 +1839,9 @@ jxlr_status jxlr_autotune(jxlr_ctx* ctx, const jxlr_batch_plan* plan, int reps,
     return JXLR_E_HIP;
   }
   const int stages[3] = {JXLR_STAGE_RECON, JXLR_STAGE_EPF, JXLR_STAGE_FINISH};
-  const void* kerns[3] = {reinterpret_cast<const void*>(recon_batch_kernel),
-                          reinterpret_cast<const void*>(epf_batch_kernel),
-                          reinterpret_cast<const void*>(finish_batch_kernel)};
+  const void* kerns[3] = {reinterpret_cast<const void*>(recon_batch_kernel<true>),
+                          reinterpret_cast<const void*>(epf_batch_kernel<true>),
+                          reinterpret_cast<const void*>(finish_batch_kernel<true>)};
   const int threads[3] = {kRecThreads, kThreads, kFinThreads};
   jxlr_launch_config out{};
   float total_ms = 0.0f;
