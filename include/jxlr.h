@@ -232,9 +232,8 @@ typedef struct jxlr_batch_plan {
 /* Schedule of the four persistent stage kernels.  grid_*: workgroup count;
  * 0 picks one workgroup per tile (per 256 regions for the block-info stage)
  * and larger values are clamped down to that.  order_*: 0 strided (tile t to
- * workgroup t mod grid); 1 XCD-contiguous (each of the eight XCDs takes one
- * contiguous eighth of the tile list, so neighbouring tiles share an L2;
- * the grid is rounded down to a multiple of 8, and below 8 order 0 is used).
+ * workgroup t mod grid); 1 XCD-contiguous (each of the eight XCDs takes about
+ * one contiguous eighth of the tile list, so neighbouring tiles share an L2).
  * The output does not depend on the schedule. */
 typedef struct jxlr_launch_config {
   int grid_info;

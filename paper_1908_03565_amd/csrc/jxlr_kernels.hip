@@ -1074,14 +1074,29 @@ __device__ __attribute__((always_inline)) inline void finish_tile(const FinishAr
 __global__ __launch_bounds__(kThreads) void blockinfo_kernel(InfoArgs a) {
   blockinfo_region(a, blockIdx.x * kThreads + threadIdx.x);
 }
-__global__ __launch_bounds__(kRecThreads) void recon_kernel(ReconArgs a) {
-  recon_tile(a, blockIdx.x, blockIdx.y);
+// Workgroups are handed to the eight XCDs round-robin (workgroup b runs on
+// XCD b mod 8).  xcd_tile(b, G) renumbers the G workgroups of a launch so
+// that each XCD takes one contiguous run of tiles: neighbouring tiles, whose
+// filter halos and partly shared cache lines overlap, then meet in the same
+// L2.  It is a bijection of [0, G) (the last G mod 8 keep their number).
+__device__ inline int xcd_tile(int b, int G) {
+  const int G8 = G & ~7;
+  return b < G8 ? (b & 7) * (G8 >> 3) + (b >> 3) : b;
 }
-__global__ __launch_bounds__(kThreads, 2) void epf_kernel(EpfArgs a) {
-  epf_tile(a, blockIdx.x, blockIdx.y);
+
+// Single-frame kernels: a 1-D grid of one workgroup per tile, tiles in row
+// order after the XCD renumbering.
+__global__ __launch_bounds__(kRecThreads) void recon_kernel(ReconArgs a, int tiles_x) {
+  const int t = xcd_tile(blockIdx.x, gridDim.x);
+  recon_tile(a, t % tiles_x, t / tiles_x);
 }
-__global__ __launch_bounds__(kFinThreads) void finish_kernel(FinishArgs a) {
-  finish_tile(a, blockIdx.x, blockIdx.y);
+__global__ __launch_bounds__(kThreads, 2) void epf_kernel(EpfArgs a, int tiles_x) {
+  const int t = xcd_tile(blockIdx.x, gridDim.x);
+  epf_tile(a, t % tiles_x, t / tiles_x);
+}
+__global__ __launch_bounds__(kFinThreads) void finish_kernel(FinishArgs a, int tiles_x) {
+  const int t = xcd_tile(blockIdx.x, gridDim.x);
+  finish_tile(a, t % tiles_x, t / tiles_x);
 }
 
 // The batch kernels share one tile list over reconstruction, EPF and finish.
@@ -1119,17 +1134,15 @@ __device__ inline int find_frame(const int* __restrict__ start, int n, int t) {
   return lo;
 }
 
-// The tiles a persistent workgroup visits.  Order 0: strided, tile t goes to
-// workgroup t mod gridDim.x.  Order 1 (gridDim.x a multiple of 8): workgroups
-// are handed to the eight XCDs round-robin, so workgroup b runs on XCD b mod 8;
-// it takes a contiguous run of the tile list such that each XCD covers one
-// contiguous eighth of it, and tiles that share filter halos share an L2.
+// The tiles a workgroup visits.  Order 0: strided, tile t goes to workgroup
+// t mod gridDim.x.  Order 1: after the xcd_tile renumbering, each workgroup
+// takes a contiguous run of the tile list, so that each XCD covers about one
+// contiguous eighth of it and tiles that share filter halos share an L2.
 struct TileRange {
   int t, end, step;
   __device__ TileRange(int order, int total) {
     if (order == 1) {
-      const int m = gridDim.x >> 3;
-      const int l = (blockIdx.x & 7) * m + (blockIdx.x >> 3);
+      const int l = xcd_tile(blockIdx.x, gridDim.x);
       t = int((long long)l * total / gridDim.x);
       end = int((long long)(l + 1) * total / gridDim.x);
       step = 1;
@@ -1573,7 +1586,8 @@ jxlr_status jxlr_reconstruct(jxlr_ctx* ctx, const jxlr_frame_params* p, const jx
   if (st) return st;
   DeviceGuard g(ctx->device);
   if (!g.ok) return JXLR_E_HIP;
-  hipLaunchKernelGGL(recon_kernel, dim3(tiles_x(p), tiles_y(p)), dim3(kRecThreads), 0, stream, a);
+  hipLaunchKernelGGL(recon_kernel, dim3(tiles_x(p) * tiles_y(p)), dim3(kRecThreads), 0, stream, a,
+                     tiles_x(p));
   return launch_status(hipGetLastError());
 }
 
@@ -1586,8 +1600,8 @@ jxlr_status jxlr_epf_pass(jxlr_ctx* ctx, const jxlr_frame_params* p, const jxlr_
   if (st) return st;
   DeviceGuard g(ctx->device);
   if (!g.ok) return JXLR_E_HIP;
-  dim3 grid((p->xsize + kEpfTW - 1) / kEpfTW, (p->ysize + kEpfTH - 1) / kEpfTH);
-  hipLaunchKernelGGL(epf_kernel, grid, dim3(kThreads), 0, stream, a);
+  hipLaunchKernelGGL(epf_kernel, dim3(tiles_x(p) * tiles_y(p)), dim3(kThreads), 0, stream, a,
+                     tiles_x(p));
   return launch_status(hipGetLastError());
 }
 
@@ -1599,7 +1613,8 @@ jxlr_status jxlr_finish(jxlr_ctx* ctx, const jxlr_frame_params* p, const jxlr_fr
   if (st) return st;
   DeviceGuard g(ctx->device);
   if (!g.ok) return JXLR_E_HIP;
-  hipLaunchKernelGGL(finish_kernel, dim3(tiles_x(p), tiles_y(p)), dim3(kFinThreads), 0, stream, a);
+  hipLaunchKernelGGL(finish_kernel, dim3(tiles_x(p) * tiles_y(p)), dim3(kFinThreads), 0, stream, a,
+                     tiles_x(p));
   return launch_status(hipGetLastError());
 }
 
@@ -1663,8 +1678,7 @@ jxlr_status check_plan(jxlr_ctx* ctx, const jxlr_batch_plan* plan) {
 
 // Enqueues one stage of a prepared batch.  grid <= 0 picks one workgroup per
 // tile (per kThreads regions for the block-info stage); larger grids are
-// clamped to that.  Order 1 needs a multiple of 8 workgroups and falls back
-// to order 0 below 8.
+// clamped to that.
 jxlr_status launch_stage(jxlr_ctx* ctx, const jxlr_batch_plan* plan, int stage, int grid,
                          int order, int epf_pass, hipStream_t stream) {
   char* base = static_cast<char*>(plan->ws);
@@ -1678,8 +1692,7 @@ jxlr_status launch_stage(jxlr_ctx* ctx, const jxlr_batch_plan* plan, int stage, 
   const int full = stage == JXLR_STAGE_INFO ? (plan->total_regions + kThreads - 1) / kThreads
                                             : plan->total_tiles;
   int gsz = grid > 0 ? std::min(grid, full) : full;
-  b.order = order == 1 && gsz >= 8 ? 1 : 0;
-  if (b.order) gsz &= ~7;
+  b.order = order == 1 ? 1 : 0;
   (void)ctx;
   const bool persist = gsz < full;
   switch (stage) {
@@ -1855,11 +1868,12 @@ jxlr_status jxlr_autotune(jxlr_ctx* ctx, const jxlr_batch_plan* plan, int reps,
     // waves of workgroups, each in both tile orders
     std::vector<std::pair<int, int>> cand;
     cand.push_back({plan->total_tiles, 0});
+    cand.push_back({plan->total_tiles, 1});
     for (int k = 1; k <= 4; ++k) {
       const int gsz = k * cus * occ;
       if (gsz >= plan->total_tiles) break;
       cand.push_back({gsz, 0});
-      cand.push_back({gsz & ~7, 1});
+      cand.push_back({gsz, 1});
     }
     float best_t = 1e30f;
     int bg = plan->total_tiles, bo = 0;
