@@ -358,6 +358,29 @@ def bench_batch(args, J, wl, torch, np):
     }
 
 
+def _sweep(args, J, wl, ctx, serving, mother, budget):
+    """Saturation sweep: arrival rates doubling from 2x the nominal one, a
+    short window each, requests cycling through a pool of pre-built inputs
+    (so that building inputs on the host is not what saturates)."""
+    res = []
+    pool_reqs = wl.c5_requests(rate=args.c5_rate, seconds=60.0)[:256]
+    pool = [wl.crop(mother, q[3], q[4], q[1], q[2], epf_iters=q[5], out_format=q[6])
+            for q in pool_reqs]
+    rate = 2 * args.c5_rate
+    for _ in range(args.c5_sweep):
+        reqs = wl.c5_requests(rate=rate, seconds=args.c5_sweep_seconds, seed=6)
+        arrivals = [(q[0], i % len(pool)) for i, q in enumerate(reqs)]
+        srv, wall = serving.run(ctx, arrivals, lambda i: pool[i], budget, split=int(args.split))
+        summ = serving.summarize(srv, wall)
+        log(f"bench: sweep {rate}/s: {summ['mp_per_s']} MP/s, p50 {summ['latency_ms']['p50']} ms, "
+            f"p99 {summ['latency_ms']['p99']} ms, mean batch {summ['mean_batch']}")
+        res.append(dict(rate_per_s=rate, offered_mp_per_s=round(
+            sum(pool[i]["xsize"] * pool[i]["ysize"] for _, i in arrivals) / 1e6 / args.c5_sweep_seconds, 2),
+            **{k: summ[k] for k in ("mp_per_s", "latency_ms", "mean_batch", "max_batch", "requests")}))
+        rate *= 2
+    return res
+
+
 def bench_serving(args, J, wl, torch, np):
     from paper_1908_03565_amd import serving
     log("bench: generating the 4096x4096 source frame of the requests")
@@ -377,6 +400,7 @@ def bench_serving(args, J, wl, torch, np):
     summ = serving.summarize(srv, wall)
     log(f"bench: {summ}")
     assert ctx.device_status() == 0
+    sweep = _sweep(args, J, wl, ctx, serving, mother, budget) if args.c5_sweep else None
     err = cpu = None
     if not args.no_check or not args.no_cpu_baseline:
         from oracle import oracle as O
@@ -433,6 +457,7 @@ def bench_serving(args, J, wl, torch, np):
                    else "f32"},
         "latency_ms": summ["latency_ms"],
         "serving": summ,
+        "saturation_sweep": sweep,
         "error": err,
         "roofline": None,
         "cpu_baseline": cpu,
@@ -453,6 +478,9 @@ def main():
     ap.add_argument("--c5-rate", type=float, default=200.0, help="serving: arrivals per second")
     ap.add_argument("--c5-seconds", type=float, default=60.0, help="serving: arrival window")
     ap.add_argument("--c5-budget-gb", type=float, default=8.0, help="serving: HBM budget (GiB)")
+    ap.add_argument("--c5-sweep", type=int, default=0,
+                    help="serving: number of doubling arrival rates to sweep after the run")
+    ap.add_argument("--c5-sweep-seconds", type=float, default=5.0)
     ap.add_argument("--split", action="store_true",
                     help="split-precision (bf16 hi+lo matrix-core) inverse transform")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
