@@ -675,6 +675,14 @@ __device__ __attribute__((always_inline)) inline void recon_tile(const ReconArgs
 // rs(y') = sum_c sad(P_c(x-1, y'), P_c(x-1+cx, y'+cy)); the strip's ten row
 // sums serve its eight overlapping patches.
 
+// a + b + c in one v_add3_u32.  Written out because the compiler otherwise
+// shares pair sums between neighbouring box sums, which costs more adds.
+__device__ inline uint32_t add3(uint32_t a, uint32_t b, uint32_t c) {
+  uint32_t r;
+  asm("v_add3_u32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+  return r;
+}
+
 struct EpfArgs {
   int W, H, Wb, Hb;
   const uint8_t* info;
@@ -902,7 +910,7 @@ __device__ __attribute__((always_inline)) inline void epf_tile(const EpfArgs& a,
       }
 #pragma unroll
       for (int i = 0; i < 8; ++i) {
-        const uint32_t sad = min(rs[i] + rs[i + 1] + rs[i + 2], 507u);
+        const uint32_t sad = min(add3(rs[i], rs[i + 1], rs[i + 2]), 507u);
         const uint32_t t = uint32_t(__mul24(int(sad), mul64) + kC);
         const float w = __uint_as_float(t >= thr ? (t & 0xFFFF0000u) : 0u);
         acc[i][3] += w;
@@ -982,28 +990,28 @@ __device__ inline void finish_store1(const FinishArgs& a, const float (&v)[3], v
   }
 }
 
-// Output rows per finish thread; a 64x32 tile takes 64 * 32 / kFinRows
-// threads.
-#ifndef JXLR_FIN_ROWS
-#define JXLR_FIN_ROWS 4
-#endif
-constexpr int kFinRows = JXLR_FIN_ROWS;
-constexpr int kFinThreads = 64 * 32 / kFinRows;
+// Output rows per finish thread (ROWS); a 64x32 tile takes 64 * 32 / ROWS
+// threads.  The single-frame kernel uses 4 rows, the batch kernel 8 (fewer
+// re-read halo rows, measured faster over many small frames).
+constexpr int kFinRowsFrame = 4, kFinRowsBatch = 8;
+template <int ROWS>
+constexpr int fin_threads() { return 64 * 32 / ROWS; }
 
 // One thread's strip: column x, output rows ys .. ys + nrows - 1 (nrows <=
-// kFinRows); gx / gy: the (mirrored) input columns x - 1 .. x + 1 and rows
-// ys - 1 .. ys + kFinRows.  The input and output planes are distinct buffers; saying so lets
+// ROWS); gx / gy: the (mirrored) input columns x - 1 .. x + 1 and rows
+// ys - 1 .. ys + ROWS.  The input and output planes are distinct buffers; saying so lets
 // the compiler issue the loads of later rows ahead of earlier stores.
+template <int ROWS>
 __device__ inline void finish_strip(const FinishArgs& a, const float* __restrict__ in,
                                     void* __restrict__ o0, void* __restrict__ o1,
                                     void* __restrict__ o2, const float* thr, int x,
-                                    const int (&gx)[3], const int (&gy)[kFinRows + 2], int ys,
+                                    const int (&gx)[3], const int (&gy)[ROWS + 2], int ys,
                                     int nrows) {
   const size_t plane = size_t(a.H) * a.stride;
   const size_t ob = size_t(ys) * a.out_stride + x;
   if (!a.gab) {
 #pragma unroll
-    for (int r = 0; r < kFinRows; ++r) {
+    for (int r = 0; r < ROWS; ++r) {
       if (r >= nrows) break;
       float v[3];
 #pragma unroll
@@ -1020,7 +1028,7 @@ __device__ inline void finish_strip(const FinishArgs& a, const float* __restrict
 #pragma unroll
       for (int j = 0; j < 3; ++j) w[r][c][j] = in[c * plane + size_t(gy[r]) * a.stride + gx[j]];
 #pragma unroll
-  for (int r = 0; r < kFinRows; ++r) {
+  for (int r = 0; r < ROWS; ++r) {
     if (r >= nrows) break;
     const int u = r % 3, m = (r + 1) % 3, d = (r + 2) % 3;
 #pragma unroll
@@ -1038,30 +1046,31 @@ __device__ inline void finish_strip(const FinishArgs& a, const float* __restrict
   }
 }
 
-// One 64x32 tile; thread = one column of a kFinRows-row strip (x0 + tid % 64,
-// rows y0 + kFinRows (tid / 64) ..), so each row of a wave is one coalesced
+// One 64x32 tile; thread = one column of a ROWS-row strip (x0 + tid % 64,
+// rows y0 + ROWS (tid / 64) ..), so each row of a wave is one coalesced
 // load per channel and neighbour column.  Indices go through the 6.5
 // mirroring only in tiles that touch the frame edge.
+template <int ROWS>
 __device__ __attribute__((always_inline)) inline void finish_tile(const FinishArgs& a, int tbx, int tby) {
   __shared__ float s_thr[257];
   const int tid = threadIdx.x;
   const int x0 = 64 * tbx, y0 = 32 * tby;
   const float* thr = a.thr;
   if (a.format == JXLR_OUT_U8_SRGB) {
-    for (int i = tid; i < 257; i += kFinThreads) s_thr[i] = a.thr[i];
+    for (int i = tid; i < 257; i += fin_threads<ROWS>()) s_thr[i] = a.thr[i];
     __syncthreads();
     thr = s_thr;
   }
-  const int x = x0 + (tid & 63), ys = y0 + kFinRows * (tid >> 6);
+  const int x = x0 + (tid & 63), ys = y0 + ROWS * (tid >> 6);
   if (x >= a.W || ys >= a.H) return;
   const bool edge = x0 == 0 || x0 + 65 > a.W || y0 == 0 || y0 + 33 > a.H;
-  int gx[3], gy[kFinRows + 2];
+  int gx[3], gy[ROWS + 2];
 #pragma unroll
   for (int j = 0; j < 3; ++j) gx[j] = edge ? mirror(x - 1 + j, a.W) : x - 1 + j;
 #pragma unroll
-  for (int r = 0; r < kFinRows + 2; ++r) gy[r] = edge ? mirror(ys - 1 + r, a.H) : ys - 1 + r;
-  finish_strip(a, a.in, a.out[0], a.out[1], a.out[2], thr, x, gx, gy, ys,
-               min(kFinRows, a.H - ys));
+  for (int r = 0; r < ROWS + 2; ++r) gy[r] = edge ? mirror(ys - 1 + r, a.H) : ys - 1 + r;
+  finish_strip<ROWS>(a, a.in, a.out[0], a.out[1], a.out[2], thr, x, gx, gy, ys,
+                     min(ROWS, a.H - ys));
 }
 
 // ---------------------------------------------------------------------------
@@ -1094,9 +1103,10 @@ __global__ __launch_bounds__(kThreads, 2) void epf_kernel(EpfArgs a, int tiles_x
   const int t = xcd_tile(blockIdx.x, gridDim.x);
   epf_tile(a, t % tiles_x, t / tiles_x);
 }
-__global__ __launch_bounds__(kFinThreads) void finish_kernel(FinishArgs a, int tiles_x) {
+__global__ __launch_bounds__(fin_threads<kFinRowsFrame>()) void finish_kernel(FinishArgs a,
+                                                                              int tiles_x) {
   const int t = xcd_tile(blockIdx.x, gridDim.x);
-  finish_tile(a, t % tiles_x, t / tiles_x);
+  finish_tile<kFinRowsFrame>(a, t % tiles_x, t / tiles_x);
 }
 
 // The batch kernels share one tile list over reconstruction, EPF and finish.
@@ -1214,7 +1224,7 @@ __global__ __launch_bounds__(kThreads, 2) void epf_batch_kernel(BatchArgs b) {
 }
 
 template <bool PERSIST>
-__global__ __launch_bounds__(kFinThreads) void finish_batch_kernel(BatchArgs b) {
+__global__ __launch_bounds__(fin_threads<kFinRowsBatch>()) void finish_batch_kernel(BatchArgs b) {
   for (TileRange r(b.order, b.tile_start[b.n]); r.t < r.end; r.t += r.step) {
     if (PERSIST) __syncthreads();
     const int f = __builtin_amdgcn_readfirstlane(b.tile_frame[r.t]);
@@ -1222,7 +1232,7 @@ __global__ __launch_bounds__(kFinThreads) void finish_batch_kernel(BatchArgs b) 
     const int lt = __builtin_amdgcn_readfirstlane(r.t - b.tile_start[f]);
     const int tx = const_load(&d->tiles_x);
     const FinishArgs a = const_load(&d->fin);
-    finish_tile(a, lt % tx, lt / tx);
+    finish_tile<kFinRowsBatch>(a, lt % tx, lt / tx);
     if (!PERSIST) break;
   }
 }
@@ -1613,7 +1623,8 @@ jxlr_status jxlr_finish(jxlr_ctx* ctx, const jxlr_frame_params* p, const jxlr_fr
   if (st) return st;
   DeviceGuard g(ctx->device);
   if (!g.ok) return JXLR_E_HIP;
-  hipLaunchKernelGGL(finish_kernel, dim3(tiles_x(p) * tiles_y(p)), dim3(kFinThreads), 0, stream, a,
+  hipLaunchKernelGGL(finish_kernel, dim3(tiles_x(p) * tiles_y(p)),
+                     dim3(fin_threads<kFinRowsFrame>()), 0, stream, a,
                      tiles_x(p));
   return launch_status(hipGetLastError());
 }
@@ -1713,9 +1724,11 @@ jxlr_status launch_stage(jxlr_ctx* ctx, const jxlr_batch_plan* plan, int stage, 
       break;
     case JXLR_STAGE_FINISH:
       if (persist)
-        hipLaunchKernelGGL(finish_batch_kernel<true>, dim3(gsz), dim3(kFinThreads), 0, stream, b);
+        hipLaunchKernelGGL(finish_batch_kernel<true>, dim3(gsz), dim3(fin_threads<kFinRowsBatch>()),
+                           0, stream, b);
       else
-        hipLaunchKernelGGL(finish_batch_kernel<false>, dim3(gsz), dim3(kFinThreads), 0, stream, b);
+        hipLaunchKernelGGL(finish_batch_kernel<false>, dim3(gsz), dim3(fin_threads<kFinRowsBatch>()),
+                           0, stream, b);
       break;
     default:
       return JXLR_E_PARAM;
@@ -1855,7 +1868,7 @@ jxlr_status jxlr_autotune(jxlr_ctx* ctx, const jxlr_batch_plan* plan, int reps,
   const void* kerns[3] = {reinterpret_cast<const void*>(recon_batch_kernel<true>),
                           reinterpret_cast<const void*>(epf_batch_kernel<true>),
                           reinterpret_cast<const void*>(finish_batch_kernel<true>)};
-  const int threads[3] = {kRecThreads, kThreads, kFinThreads};
+  const int threads[3] = {kRecThreads, kThreads, fin_threads<kFinRowsBatch>()};
   jxlr_launch_config out{};
   float total_ms = 0.0f;
   for (int si = 0; si < 3 && !st; ++si) {
