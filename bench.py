@@ -364,7 +364,7 @@ def _sweep(args, J, wl, ctx, serving, mother, budget):
     (so that building inputs on the host is not what saturates)."""
     res = []
     pool_reqs = wl.c5_requests(rate=args.c5_rate, seconds=60.0)[:256]
-    pool = [wl.crop(mother, q[3], q[4], q[1], q[2], epf_iters=q[5], out_format=q[6])
+    pool = [J.pin_frame(wl.crop(mother, q[3], q[4], q[1], q[2], epf_iters=q[5], out_format=q[6]))
             for q in pool_reqs]
     rate = 2 * args.c5_rate
     for _ in range(args.c5_sweep):

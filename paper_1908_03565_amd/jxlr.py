@@ -195,9 +195,20 @@ def _stream_handle(stream):
 class DeviceFrame:
     """A frame's input planes resident in device memory (torch tensors)."""
 
-    def __init__(self, frame, device="cuda"):
+    PLANES = (("ac", np.int32), ("dc", np.int32), ("strategy", np.uint8), ("qf", np.uint8),
+              ("sharpness", np.uint8), ("cfl_kx", np.float32), ("cfl_kb", np.float32))
+
+    def __init__(self, frame, device="cuda", non_blocking=False):
+        """frame: dict of numpy arrays, or of CPU tensors (pinned ones can be
+        copied with non_blocking=True on the current stream; the caller keeps
+        them alive until that copy has run)."""
         import torch
-        t = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a, dtype=dt)).to(device)
+
+        def t(a, dt):
+            if isinstance(a, torch.Tensor):
+                return a.to(device, non_blocking=non_blocking)
+            return torch.from_numpy(np.ascontiguousarray(a, dtype=dt)).to(device)
+
         self.xsize, self.ysize = int(frame["xsize"]), int(frame["ysize"])
         self.ac = t(frame["ac"], np.int32)
         self.dc = t(frame["dc"], np.int32)
@@ -378,3 +389,16 @@ class Graph:
             self.close()
         except Exception:
             pass
+
+
+def pin_frame(frame):
+    """A copy of a frame dict whose planes are pinned CPU tensors (for
+    asynchronous uploads)."""
+    import torch
+    out = dict(frame)
+    for k, dt in DeviceFrame.PLANES:
+        a = np.ascontiguousarray(frame[k], dtype=dt)
+        t = torch.empty(a.shape, dtype=getattr(torch, np.dtype(dt).name), pin_memory=True)
+        t.numpy()[...] = a
+        out[k] = t
+    return out

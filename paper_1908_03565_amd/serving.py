@@ -5,7 +5,8 @@ memory) arrive over time.  The server
 
   * admits waiting requests in arrival order while their device footprint
     (inputs, workspace, outputs) fits the HBM budget;
-  * uploads each admitted request's inputs on an upload stream;
+  * uploads each admitted request's inputs (pinned host memory) on an upload
+    stream, asynchronously;
   * gathers every uploaded request that is not yet running into one batch
     and launches it (block info, reconstruction, EPF passes, finish as
     persistent kernels over the batch's tiles) on the next of several compute
@@ -89,11 +90,12 @@ class Server:
             self.used += r.fp
             self.peak_used = max(self.peak_used, self.used)
             with torch.cuda.stream(self.up_stream):
-                r.df = J.DeviceFrame(r.frame, device=self.dev)
+                # pinned planes upload asynchronously; the request keeps them
+                # until its output is back
+                r.df = J.DeviceFrame(r.frame, device=self.dev, non_blocking=True)
                 r.out = self.ctx.empty_out(r.params)
                 r.ev_up = torch.cuda.Event()
                 r.ev_up.record(self.up_stream)
-            r.frame = None if not r.keep else r.frame
             self.uploaded.append(r)
         if self.waiting and not self.uploaded and not self.running and not self.copying:
             # nothing in flight and the head does not fit: it can never fit
@@ -143,6 +145,7 @@ class Server:
                 r.df = r.out = None
                 if not r.keep:
                     r.host_out = None
+                    r.frame = None
                 self.done.append(r)
             else:
                 rest.append(r)
@@ -172,6 +175,8 @@ def run(ctx, arrivals, make_frame, budget_bytes, split=0, max_batch=64, n_stream
     def produce():
         for i, (t, recipe) in enumerate(arrivals):
             fr = make_frame(recipe)
+            if not isinstance(fr["ac"], srv.torch.Tensor):
+                fr = J.pin_frame(fr)  # inputs arrive in pinned host memory
             p = J.params(fr["xsize"], fr["ysize"], out_format=fr["out_format"], idct_split=split,
                          **fr["params"])
             keep = keep_every > 0 and i % keep_every == 0
