@@ -53,18 +53,51 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def roofline_of(kernels, weights):
+# HBM traffic per launch of each workload's dominant kernel, from two
+# rocprofv3 --pmc passes over `bench.py --workload W --steps 3 --warmup 1
+# --no-check --no-cpu-baseline` (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch,
+# averaged over the dispatches), each scaled by what the same counter reads
+# for a plain device copy of known size (`bench.py --copy-probe 256`).  The
+# figures hold for the kernel sources they were taken on (hash below) and are
+# reported as null for any other.
+PMC_COPY_SCALE = {"FETCH_SIZE": 2.0, "WRITE_SIZE": 1.0}
+PMC_SOURCES = ("paper_1908_03565_amd/csrc/jxlr_kernels.hip", "paper_1908_03565_amd/csrc/jxlr_tables.cpp",
+               "paper_1908_03565_amd/csrc/jxlr_tables.h", "paper_1908_03565_amd/csrc/gen_dct_consts.py")
+PMC_SOURCES_SHA256 = None
+PMC_KIB = {}  # (workload name, kernel) -> (FETCH_SIZE KiB, WRITE_SIZE KiB) per dispatch
+
+
+def sources_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    for f in PMC_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def traffic_bytes(workload, kernel):
+    kib = PMC_KIB.get((workload, kernel))
+    if kib is None or PMC_SOURCES_SHA256 is None or sources_sha256() != PMC_SOURCES_SHA256:
+        return None
+    return int(round(1024 * (kib[0] * PMC_COPY_SCALE["FETCH_SIZE"] + kib[1] * PMC_COPY_SCALE["WRITE_SIZE"])))
+
+
+def roofline_of(kernels, weights, workload=None, px=None):
     """kernels: name -> dict(ms, bound, achieved); weights: launches per step."""
     dominant = max(kernels, key=lambda k: kernels[k]["ms"] * weights.get(k, 1))
     dk = kernels[dominant]
+    traffic = traffic_bytes(workload, dominant)
     if dk["bound"] == "alu":
         return dict(bound="alu", kernel=dominant, achieved=round(dk["achieved"], 3),
                     peak=round(ALU_PEAK_TOPS, 3), unit="Top/s",
                     frac=round(dk["achieved"] / ALU_PEAK_TOPS, 4), avg_ms=round(dk["ms"], 5),
-                    ops_per_px=EPF_OPS_PER_PX, traffic=None)
+                    ops_per_px=EPF_OPS_PER_PX, traffic=traffic,
+                    algorithmic_bytes=24 * px if px else None)
     return dict(bound="hbm", kernel=dominant, achieved=round(dk["achieved"], 1), peak=HBM_PEAK_GBS,
                 unit="GB/s", frac=round(dk["achieved"] / HBM_PEAK_GBS, 4),
-                avg_ms=round(dk["ms"], 5), bytes_per_px=dk.get("bytes_per_px"), traffic=None)
+                avg_ms=round(dk["ms"], 5), bytes_per_px=dk.get("bytes_per_px"), traffic=traffic,
+                algorithmic_bytes=dk.get("bytes_per_px") * px if px else None)
 
 
 def kernel_table(px, recon_ms, epf_ms, fin_ms, out_format, names):
@@ -135,7 +168,7 @@ def bench_frame(args, J, wl, torch, np):
 
     kernels = kernel_table(W * H, recon_ms, statistics.mean(epf_ms) if n_epf else None, fin_ms,
                            p.out_format, ("recon_kernel", "epf_kernel", "finish_kernel"))
-    roofline = roofline_of(kernels, {"epf_kernel": n_epf})
+    roofline = roofline_of(kernels, {"epf_kernel": n_epf}, frame["name"], W * H)
 
     err = None
     cpu = None
@@ -271,7 +304,7 @@ def bench_batch(args, J, wl, torch, np):
     fmt = ps[0].out_format
     kernels = kernel_table(px, recon_ms, statistics.mean(epf_ms) if n_epf else None, fin_ms, fmt,
                            ("recon_batch_kernel", "epf_batch_kernel", "finish_batch_kernel"))
-    roofline = roofline_of(kernels, {"epf_batch_kernel": n_epf})
+    roofline = roofline_of(kernels, {"epf_batch_kernel": n_epf}, name, px)
 
     # every frame of the batch equals its single-frame decode; a sample of
     # frames against the oracle
