@@ -63,8 +63,17 @@ def log(msg):
 PMC_COPY_SCALE = {"FETCH_SIZE": 2.0, "WRITE_SIZE": 1.0}
 PMC_SOURCES = ("paper_1908_03565_amd/csrc/jxlr_kernels.hip", "paper_1908_03565_amd/csrc/jxlr_tables.cpp",
                "paper_1908_03565_amd/csrc/jxlr_tables.h", "paper_1908_03565_amd/csrc/gen_dct_consts.py")
-PMC_SOURCES_SHA256 = None
-PMC_KIB = {}  # (workload name, kernel) -> (FETCH_SIZE KiB, WRITE_SIZE KiB) per dispatch
+PMC_SOURCES_SHA256 = "b62b14fadaa2c7e789cf539b0d8e3510a9956233facd3be7f529ac2cd539418c"
+# (workload name, kernel) -> (FETCH_SIZE KiB, WRITE_SIZE KiB) per dispatch
+PMC_KIB = {
+    ("c2_2048x2048_mixed_epf2", "epf_kernel"): (25479.3, 49152.0),
+    ("c2_2048x2048_mixed_epf2", "recon_kernel"): (25470.8, 49152.0),
+    ("c2_2048x2048_mixed_epf2", "finish_kernel"): (24849.0, 49152.0),
+    ("c3_4096x4096_half_dct32", "epf_kernel"): (101210.3, 196608.2),
+    ("c4_batch64_loguniform_256_3072_epf1_u8srgb", "epf_batch_kernel"): (1099745.9, 1051484.5),
+    ("c1x1024_256x256_dct8", "recon_batch_kernel"): (427036.9, 786442.4),
+    ("c1x1024_256x256_dct8", "finish_batch_kernel"): (850215.8, 786432.0),
+}
 
 
 def sources_sha256():
