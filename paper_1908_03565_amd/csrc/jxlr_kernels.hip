@@ -713,7 +713,7 @@ __device__ inline uint32_t guide_byte(float v, float minv, float scale) {
   // J.2.2 in binary32: floor(clamp((v - min) * scale, 0, 255))
   const float sc = (v - minv) * scale;
   const float g = fminf(fmaxf(sc, 0.0f), 255.0f);
-  return uint32_t(floorf(g));
+  return uint32_t(g);  // truncation is the floor on [0, 255]
 }
 
 // One 64x32 output tile of an EPF pass.  Threads may return after the last
@@ -924,7 +924,10 @@ __device__ __attribute__((always_inline)) inline void epf_tile(const EpfArgs& a,
   for (int i = 0; i < 8; ++i)
     if (i < nrows)
 #pragma unroll
-      for (int c = 0; c < 3; ++c) o0[c * plane + size_t(i) * a.stride] = acc[i][c] / acc[i][3];
+      for (int c = 0; c < 3; ++c)
+        // J.2.5 normalization; the weight total is in [1, 56] (the centre
+        // weight 1 always passes), so the hardware reciprocal (1 ulp) serves
+        o0[c * plane + size_t(i) * a.stride] = acc[i][c] * __builtin_amdgcn_rcpf(acc[i][3]);
 }
 
 // ---------------------------------------------------------------------------

@@ -228,3 +228,47 @@ def test_ill_formed_map_sets_device_flag(ctx):
     g["strategy"][0, 1] = wl.DCT8
     ref = O.reconstruct(q, g)
     np.testing.assert_allclose(x[:, 32:, :], ref[:, 32:, :], atol=XYB_TOL)
+
+
+@pytest.mark.parametrize("case", ["overlap", "bad_type", "out_of_bounds"])
+def test_ill_formed_map_cases_on_device(ctx, case):
+    """The device scan finds the same ill-formed maps as the host validator:
+    overlapping varblocks, an unknown type, a varblock past the frame edge.
+    The flag is set, the region's info bytes are 0xFF, its samples 0, and the
+    other regions match the oracle."""
+    from paper_1908_03565_amd import jxlr as J
+    W = H = 64 if case != "out_of_bounds" else 56
+    # constant quant field, so that the host validator reaches the map error
+    f = wl.frame(W, H, seed=3, choices=[wl.DCT8], epf_iters=0, qf_const=8)
+    f["strategy"] = f["strategy"].copy()
+    if case == "overlap":
+        f["strategy"][0, 1] = wl.DCT8X16   # covers blocks (1, 0) and (1, 1)
+        f["strategy"][1, 0] = wl.DCT16X8   # covers (0, 1) and (1, 1): overlap
+        expect = 4
+    elif case == "bad_type":
+        f["strategy"][2, 1] = 13
+        expect = 3
+    else:
+        f["strategy"][6, 6] = wl.DCT16     # 56x56: blocks 6..7 do not exist
+        expect = 4
+    p = J.params(W, H, **f["params"])
+    assert J.validate_maps_host(p, f) == expect
+    assert ctx.device_status() == 0
+    df = J.DeviceFrame(f)
+    info = ctx.empty_info(p)
+    ctx.block_info(p, df, info)
+    xyb = ctx.empty_xyb(p)
+    ctx.reconstruct(p, df, info, xyb)
+    assert ctx.device_status() == 10
+    inf = info.cpu().numpy()
+    bad = (slice(0, 4), slice(0, 4)) if case != "out_of_bounds" else (slice(4, 7), slice(4, 7))
+    assert np.all(inf[bad] == 0xFF)
+    x = xyb.cpu().numpy()
+    px = tuple(slice(8 * s.start, 8 * s.stop) for s in bad)
+    assert np.all(x[:, px[0], px[1]] == 0)
+    g = dict(f)
+    g["strategy"] = np.full_like(f["strategy"], wl.DCT8)
+    ref = O.reconstruct(O.params(W, H, **f["params"]), g)
+    good = np.ones((H, W), bool)
+    good[px[0], px[1]] = False
+    assert np.abs(x - ref)[:, good].max() <= XYB_TOL * 4
