@@ -596,10 +596,13 @@ __device__ __attribute__((always_inline)) inline void recon_tile(const ReconArgs
   }
   __syncthreads();
 
-  // Column pass: lane = tile column, wave = channel; the column's varblock
-  // segments one after the other.
+  // Column and row passes: thread t works on region t / 96, channel
+  // (t mod 96) / 32 and column (row) t mod 32, so that two of the three waves
+  // see a single region (one transform type in the usual case) and only the
+  // middle one spans both.
+  // Column pass: the column's varblock segments one after the other.
   {
-    const int c = wave, X = lane, r = X >> 5;
+    const int r = tid / 96, c = (tid - 96 * r) >> 5, X = 32 * r + (tid & 31);
     for (int br = 0; br < 4; ++br) {
       const int lb = br * 4 + ((X & 31) >> 3);
       const int s = s_strat[r][lb];
@@ -610,9 +613,9 @@ __device__ __attribute__((always_inline)) inline void recon_tile(const ReconArgs
   }
   __syncthreads();
 
-  // Row pass: lane = (region, row).
+  // Row pass.
   {
-    const int c = wave, r = lane >> 5, Y = lane & 31;
+    const int r = tid / 96, c = (tid - 96 * r) >> 5, Y = tid & 31;
     for (int bc = 0; bc < 4; ++bc) {
       const int lb = (Y >> 3) * 4 + bc;
       const int s = s_strat[r][lb];
