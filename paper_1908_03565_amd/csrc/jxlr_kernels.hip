@@ -23,6 +23,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/jxlr.h"
@@ -337,18 +338,29 @@ __device__ inline int dq_off_lut(int s) {
 // accumulator q of lane l is C[8 (q / 4) + 4 (l / 32) + q mod 4][l mod 32].
 
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
-typedef short s16x8 __attribute__((ext_vector_type(8)));
 typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
 
-__device__ inline uint32_t bf16_bits(float x) {
-  const uint32_t u = __float_as_uint(x);
-  return (u + 0x7FFFu + ((u >> 16) & 1u)) >> 16;  // round to nearest even
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// High and low bfloat16 parts of two samples, packed two per word: hi =
+// RNE(v) and lo = RNE(v - hi) (the difference is exact in binary32).  The
+// conversions are the hardware's round-to-nearest-even packed convert.
+__device__ inline void split2(float v0, float v1, uint32_t& hi, uint32_t& lo) {
+  const f32x2 v = {v0, v1};
+  const bf16x2 h = __builtin_convertvector(v, bf16x2);
+  const f32x2 r = v - __builtin_convertvector(h, f32x2);
+  hi = __builtin_bit_cast(uint32_t, h);
+  lo = __builtin_bit_cast(uint32_t, __builtin_convertvector(r, bf16x2));
 }
 
 // One wave transforms the 32x32 block of cf starting at column col0, in
 // place.  Acol / Arow: the DeviceTables::mfma_a operands [part][step][lane][8]
-// of the column and row matrices.  Every wave of the workgroup calls this
-// the same number of times (it holds workgroup barriers).
+// of the column and row matrices.  Only the calling wave touches the block,
+// and the LDS accesses of one wave complete in issue order, so the reads of
+// the second product see the first product's stores without a workgroup
+// barrier; the caller synchronizes before other waves read the block.
 __device__ inline void mfma_region(float (*cf)[kRecLd], int col0, const uint16_t* __restrict__ Acol,
                                    const uint16_t* __restrict__ Arow, int lane) {
   const int j = lane & 31, kh = lane >> 5;
@@ -362,22 +374,24 @@ __device__ inline void mfma_region(float (*cf)[kRecLd], int col0, const uint16_t
     for (int step = 0; step < 2; ++step) {
       const bf16x8 ah = *reinterpret_cast<const bf16x8*>(A + ((0 * 2 + step) * 64 + lane) * 8);
       const bf16x8 al = *reinterpret_cast<const bf16x8*>(A + ((1 * 2 + step) * 64 + lane) * 8);
-      s16x8 bh, bl;
+      u32x4 bh, bl;
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const int k = 16 * step + 8 * kh + e;
+      for (int e = 0; e < 4; ++e) {
+        const int k = 16 * step + 8 * kh + 2 * e;
         // pass 0: B = K[k][j]; pass 1: B = Y^T[k][j] = Y[j][k]
-        const float v = pass == 0 ? cf[k][col0 + j] : cf[j][col0 + k];
-        const uint32_t h = bf16_bits(v);
-        bh[e] = short(h);
-        bl[e] = short(bf16_bits(v - __uint_as_float(h << 16)));
+        const float v0 = pass == 0 ? cf[k][col0 + j] : cf[j][col0 + k];
+        const float v1 = pass == 0 ? cf[k + 1][col0 + j] : cf[j][col0 + k + 1];
+        uint32_t h, l;
+        split2(v0, v1, h, l);
+        bh[e] = h;
+        bl[e] = l;
       }
       const bf16x8 bH = __builtin_bit_cast(bf16x8, bh), bL = __builtin_bit_cast(bf16x8, bl);
       acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bH, acc, 0, 0, 0);
       acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bL, acc, 0, 0, 0);
       acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bH, acc, 0, 0, 0);
     }
-    __syncthreads();  // every lane has read its operands
+    // the stores depend on every read of this pass through acc
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
       const int i = 8 * (q >> 2) + 4 * kh + (q & 3);
@@ -385,7 +399,7 @@ __device__ inline void mfma_region(float (*cf)[kRecLd], int col0, const uint16_t
       if (pass == 0) cf[i][col0 + j] = acc[q];
       else cf[j][col0 + i] = acc[q];
     }
-    __syncthreads();
+    __builtin_amdgcn_wave_barrier();
   }
 }
 
@@ -634,6 +648,7 @@ __device__ __attribute__((always_inline)) inline void recon_tile(const ReconArgs
       mfma_region(coef[wave], 32 * r, &T->mfma_a[m & 3][0][0][0][0], &T->mfma_a[m >> 2][0][0][0][0],
                   lane);
     }
+    __syncthreads();
   }
 
   // Crop (6.2) and store, the thread's groups again; an ill-formed region is
@@ -686,6 +701,25 @@ __device__ inline uint32_t add3(uint32_t a, uint32_t b, uint32_t c) {
   return r;
 }
 
+// (a <= b) ? (t with its low 16 bits cleared) : 0, as one compare and one
+// v_cndmask_b32 whose SDWA selects move the high half of t into the high
+// half of the result and zero the rest.
+__device__ inline uint32_t select_hi(uint32_t a, uint32_t b, uint32_t t) {
+  uint32_t r;
+  asm("v_cmp_le_u32 vcc, %1, %2\n\t"
+      "v_cndmask_b32_sdwa %0, 0, %3, vcc dst_sel:WORD_1 dst_unused:UNUSED_PAD src0_sel:DWORD "
+      "src1_sel:WORD_1"
+      : "=v"(r)
+      : "v"(a), "v"(b), "v"(t)
+      : "vcc");
+  return r;
+}
+
+// Weight(sad, mul) of J.2.4, ((min(sad,507) << 6) * mul >> 16) + (127 << 7),
+// placed in the top half of a binary32 pattern, equals
+// (min(sad,507) * 64 mul + (127 << 23)) with the low 16 bits cleared.
+constexpr uint32_t kEpfC = 127u << 23;
+
 struct EpfArgs {
   int W, H, Wb, Hb;
   const uint8_t* info;
@@ -727,6 +761,8 @@ __device__ __attribute__((always_inline)) inline void epf_tile(const EpfArgs& a,
   __shared__ uint32_t s_w[3][kPH][kGW + 1];
   __shared__ float s_rng[32];
   __shared__ int s_mul[32];
+  __shared__ uint32_t s_sadmax[32];
+  __shared__ int s_clamp;
   __shared__ uint8_t s_owner[2][16], s_strat[2][16];
   __shared__ int s_bad[2];
 
@@ -783,6 +819,7 @@ __device__ __attribute__((always_inline)) inline void epf_tile(const EpfArgs& a,
     }
   }
   if (tid < 2) s_bad[tid] = 0;
+  if (tid == 2) s_clamp = 0;
   __syncthreads();
 
   // B: guide words at every start column (four per aligned word pair).
@@ -850,7 +887,15 @@ __device__ __attribute__((always_inline)) inline void epf_tile(const EpfArgs& a,
       sg = fminf(sg, a.sigma_max);
       sig = int(sg);  // truncation; sg >= 0
     }
-    s_mul[tid] = sig >= 16 ? a.mul_table[sig] * 64 : 1;
+    // The weight falls with the SAD (mul <= 0), so it passes the threshold
+    // exactly for SAD <= (kEpfC - thr) / (-64 mul).  Below 507 that bound
+    // also makes the clamp at 507 irrelevant; a tile with any larger bound
+    // takes the clamped form.
+    const int mul = sig >= 16 ? a.mul_table[sig] : 0;
+    s_mul[tid] = sig >= 16 ? mul * 64 : 1;
+    const uint32_t smax = mul < 0 ? (kEpfC - a.thr) / uint32_t(-64 * mul) : 0xFFFFFFFFu;
+    s_sadmax[tid] = smax;
+    if (sig >= 16 && smax >= 507) s_clamp = 1;
     if (a.sigma_dbg && bx < a.Wb && by < a.Hb) a.sigma_dbg[size_t(by) * a.Wb + bx] = sig;
   }
   __syncthreads();
@@ -875,11 +920,7 @@ __device__ __attribute__((always_inline)) inline void epf_tile(const EpfArgs& a,
         o0[c * plane + size_t(i) * a.stride] = s_in[c][8 * strip + 3 + i][lx + 3];
     return;
   }
-  // Weight(sad, mul) of J.2.4: ((min(sad,507) << 6) * mul >> 16) + (127 << 7),
-  // placed in the top half of a binary32 pattern, equals
-  // (min(sad,507) * 64 mul + (127 << 23)) with the low 16 bits cleared.
-  constexpr int kC = 127 << 23;
-  const uint32_t thr = a.thr;
+  const uint32_t thr = a.thr, smax = s_sadmax[strip * 8 + (lx >> 3)];
   uint32_t ref[10][3];
 #pragma unroll
   for (int j = 0; j < 10; ++j)
@@ -891,38 +932,56 @@ __device__ __attribute__((always_inline)) inline void epf_tile(const EpfArgs& a,
 #pragma unroll
     for (int c = 0; c < 4; ++c) acc[i][c] = 0.0f;
 
-  for (int cx = -3; cx <= 4; ++cx) {
-    uint32_t nb[16][3];
-    float inp[14][3];
+  // The 56 window offsets; CLAMP (uniform over the workgroup) selects the
+  // form with the clamp at 507 and the threshold on the weight pattern, the
+  // other form thresholds the SAD itself (where it passes, it is below 507;
+  // where it does not, the unclamped product is discarded).
+  auto accumulate = [&](auto clamp_tag) {
+    constexpr bool CLAMP = decltype(clamp_tag)::value;
+    for (int cx = -3; cx <= 4; ++cx) {
+      uint32_t nb[16][3];
+      float inp[14][3];
 #pragma unroll
-    for (int j = 0; j < 16; ++j)
+      for (int j = 0; j < 16; ++j)
 #pragma unroll
-      for (int c = 0; c < 3; ++c) nb[j][c] = s_p[c][8 * strip + j][lx + 3 + cx];
+        for (int c = 0; c < 3; ++c) nb[j][c] = s_p[c][8 * strip + j][lx + 3 + cx];
 #pragma unroll
-    for (int j = 0; j < 14; ++j)
+      for (int j = 0; j < 14; ++j)
 #pragma unroll
-      for (int c = 0; c < 3; ++c) inp[j][c] = s_in[c][8 * strip + j][lx + 3 + cx];
+        for (int c = 0; c < 3; ++c) inp[j][c] = s_in[c][8 * strip + j][lx + 3 + cx];
 #pragma unroll
-    for (int cy = -3; cy <= 3; ++cy) {
-      uint32_t rs[10];
+      for (int cy = -3; cy <= 3; ++cy) {
+        uint32_t rs[10];
 #pragma unroll
-      for (int j = 0; j < 10; ++j) {
-        uint32_t s = __builtin_amdgcn_sad_u8(ref[j][0], nb[j + cy + 3][0], 0u);
-        s = __builtin_amdgcn_sad_u8(ref[j][1], nb[j + cy + 3][1], s);
-        rs[j] = __builtin_amdgcn_sad_u8(ref[j][2], nb[j + cy + 3][2], s);
-      }
+        for (int j = 0; j < 10; ++j) {
+          uint32_t s = __builtin_amdgcn_sad_u8(ref[j][0], nb[j + cy + 3][0], 0u);
+          s = __builtin_amdgcn_sad_u8(ref[j][1], nb[j + cy + 3][1], s);
+          rs[j] = __builtin_amdgcn_sad_u8(ref[j][2], nb[j + cy + 3][2], s);
+        }
 #pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const uint32_t sad = min(add3(rs[i], rs[i + 1], rs[i + 2]), 507u);
-        const uint32_t t = uint32_t(__mul24(int(sad), mul64) + kC);
-        const float w = __uint_as_float(t >= thr ? (t & 0xFFFF0000u) : 0u);
-        acc[i][3] += w;
-        acc[i][0] = fmaf(w, inp[i + cy + 3][0], acc[i][0]);
-        acc[i][1] = fmaf(w, inp[i + cy + 3][1], acc[i][1]);
-        acc[i][2] = fmaf(w, inp[i + cy + 3][2], acc[i][2]);
+        for (int i = 0; i < 8; ++i) {
+          const uint32_t sad = add3(rs[i], rs[i + 1], rs[i + 2]);
+          uint32_t wb;
+          if constexpr (CLAMP) {
+            const uint32_t t = uint32_t(__mul24(int(min(sad, 507u)), mul64)) + kEpfC;
+            wb = select_hi(thr, t, t);
+          } else {
+            const uint32_t t = uint32_t(__mul24(int(sad), mul64)) + kEpfC;
+            wb = select_hi(sad, smax, t);
+          }
+          const float w = __uint_as_float(wb);
+          acc[i][3] += w;
+          acc[i][0] = fmaf(w, inp[i + cy + 3][0], acc[i][0]);
+          acc[i][1] = fmaf(w, inp[i + cy + 3][1], acc[i][1]);
+          acc[i][2] = fmaf(w, inp[i + cy + 3][2], acc[i][2]);
+        }
       }
     }
-  }
+  };
+  if (s_clamp)
+    accumulate(std::true_type{});
+  else
+    accumulate(std::false_type{});
 #pragma unroll
   for (int i = 0; i < 8; ++i)
     if (i < nrows)
