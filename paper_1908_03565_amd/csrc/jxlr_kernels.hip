@@ -1030,29 +1030,27 @@ __device__ inline int srgb_code(float v, const float* __restrict__ thr, int maxv
   return c;
 }
 
-// XYB -> RGB (L.2) of one pixel (v: X, Y, B after Gaborish) and its store at
-// element offset o of the output planes o0..o2, in the output format.
-__device__ inline void finish_store1(const FinishArgs& a, const float (&v)[3], void* o0, void* o1,
-                                     void* o2, size_t o, const float* thr) {
+// XYB -> RGB (L.2) of one pixel (v: X, Y, B after Gaborish).
+__device__ inline void xyb_to_rgb(const FinishArgs& a, const float (&v)[3], float (&rgb)[3]) {
   const float gr = v[1] + v[0], gg = v[1] - v[0], gb = v[2];
   const float mr = fmaf(gr * gr, gr, a.bias[0]);
   const float mg = fmaf(gg * gg, gg, a.bias[1]);
   const float mb = fmaf(gb * gb, gb, a.bias[2]);
-  float rgb[3];
 #pragma unroll
   for (int r = 0; r < 3; ++r) rgb[r] = fmaf(a.m[3 * r], mr, fmaf(a.m[3 * r + 1], mg, a.m[3 * r + 2] * mb));
-  void* dst[3] = {o0, o1, o2};
-  if (a.format == JXLR_OUT_F32) {
-#pragma unroll
-    for (int c = 0; c < 3; ++c) static_cast<float*>(dst[c])[o] = rgb[c];
-  } else if (a.format == JXLR_OUT_U8_SRGB) {
-#pragma unroll
-    for (int c = 0; c < 3; ++c) static_cast<uint8_t*>(dst[c])[o] = uint8_t(srgb_code(rgb[c], thr, 255));
-  } else {
-#pragma unroll
-    for (int c = 0; c < 3; ++c)
-      static_cast<uint16_t*>(dst[c])[o] = uint16_t(srgb_code(rgb[c], thr, 65535));
-  }
+}
+
+// Output sample type of each format.
+template <int FMT> struct OutT;
+template <> struct OutT<JXLR_OUT_F32> { using T = float; };
+template <> struct OutT<JXLR_OUT_U8_SRGB> { using T = uint8_t; };
+template <> struct OutT<JXLR_OUT_U16_SRGB> { using T = uint16_t; };
+
+template <int FMT>
+__device__ inline typename OutT<FMT>::T encode_out(float v, const float* __restrict__ thr) {
+  if constexpr (FMT == JXLR_OUT_F32) return v;
+  else if constexpr (FMT == JXLR_OUT_U8_SRGB) return uint8_t(srgb_code(v, thr, 255));
+  else return uint16_t(srgb_code(v, thr, 65535));
 }
 
 // Output rows per finish thread (ROWS); a 64x32 tile takes 64 * 32 / ROWS
@@ -1063,43 +1061,77 @@ template <int ROWS>
 constexpr int fin_threads() { return 64 * 32 / ROWS; }
 
 // One thread's strip: column x, output rows ys .. ys + nrows - 1 (nrows <=
-// ROWS); gx / gy: the (mirrored) input columns x - 1 .. x + 1 and rows
-// ys - 1 .. ys + ROWS.  The input and output planes are distinct buffers; saying so lets
-// the compiler issue the loads of later rows ahead of earlier stores.
-template <int ROWS>
+// ROWS), in output format FMT.  EDGE: the 3x3 window may leave the frame
+// and its indices go through the 6.5 mirroring; otherwise every row of a
+// channel is one pointer, advanced by the stride, with the neighbour columns
+// at offsets -1 and +1.  The input and output planes are distinct buffers;
+// saying so lets the compiler issue the loads of later rows ahead of earlier
+// stores.
+template <int ROWS, int FMT, bool EDGE>
 __device__ inline void finish_strip(const FinishArgs& a, const float* __restrict__ in,
                                     void* __restrict__ o0, void* __restrict__ o1,
-                                    void* __restrict__ o2, const float* thr, int x,
-                                    const int (&gx)[3], const int (&gy)[ROWS + 2], int ys,
-                                    int nrows) {
+                                    void* __restrict__ o2, const float* __restrict__ thr, int x,
+                                    int ys, int nrows) {
+  using T = typename OutT<FMT>::T;
   const size_t plane = size_t(a.H) * a.stride;
-  const size_t ob = size_t(ys) * a.out_stride + x;
+  T* out[3] = {static_cast<T*>(o0) + size_t(ys) * a.out_stride + x,
+               static_cast<T*>(o1) + size_t(ys) * a.out_stride + x,
+               static_cast<T*>(o2) + size_t(ys) * a.out_stride + x};
+  auto store = [&](int r, const float (&v)[3]) {
+    float rgb[3];
+    xyb_to_rgb(a, v, rgb);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) out[c][size_t(r) * a.out_stride] = encode_out<FMT>(rgb[c], thr);
+  };
   if (!a.gab) {
+    const float* p = in + size_t(ys) * a.stride + x;
 #pragma unroll
     for (int r = 0; r < ROWS; ++r) {
       if (r >= nrows) break;
       float v[3];
 #pragma unroll
-      for (int c = 0; c < 3; ++c) v[c] = in[c * plane + size_t(gy[r + 1]) * a.stride + x];
-      finish_store1(a, v, o0, o1, o2, ob + size_t(r) * a.out_stride, thr);
+      for (int c = 0; c < 3; ++c) v[c] = p[c * plane + size_t(r) * a.stride];
+      store(r, v);
     }
     return;
   }
+  // rows ys - 1 .. ys + ROWS and columns x - 1 .. x + 1 of the input
+  const float* rowp[3];
+  int gx[3] = {x - 1, x, x + 1}, gy[ROWS + 2];
+#pragma unroll
+  for (int r = 0; r < ROWS + 2; ++r) gy[r] = ys - 1 + r;
+  if constexpr (EDGE) {
+#pragma unroll
+    for (int j = 0; j < 3; ++j) gx[j] = mirror(gx[j], a.W);
+#pragma unroll
+    for (int r = 0; r < ROWS + 2; ++r) gy[r] = mirror(gy[r], a.H);
+  } else {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) rowp[c] = in + c * plane + size_t(ys - 1) * a.stride + x;
+  }
+  auto load_row = [&](int r, float (&w)[3][3]) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      if constexpr (EDGE) {
+        const float* q = in + c * plane + size_t(gy[r]) * a.stride;
+#pragma unroll
+        for (int j = 0; j < 3; ++j) w[c][j] = q[gx[j]];
+      } else {
+        const float* q = rowp[c] + size_t(r) * a.stride;
+        w[c][0] = q[-1];
+        w[c][1] = q[0];
+        w[c][2] = q[1];
+      }
+    }
+  };
   float w[3][3][3];  // rolling rows [slot][channel][column]
-#pragma unroll
-  for (int r = 0; r < 2; ++r)
-#pragma unroll
-    for (int c = 0; c < 3; ++c)
-#pragma unroll
-      for (int j = 0; j < 3; ++j) w[r][c][j] = in[c * plane + size_t(gy[r]) * a.stride + gx[j]];
+  load_row(0, w[0]);
+  load_row(1, w[1]);
 #pragma unroll
   for (int r = 0; r < ROWS; ++r) {
     if (r >= nrows) break;
     const int u = r % 3, m = (r + 1) % 3, d = (r + 2) % 3;
-#pragma unroll
-    for (int c = 0; c < 3; ++c)
-#pragma unroll
-      for (int j = 0; j < 3; ++j) w[d][c][j] = in[c * plane + size_t(gy[r + 2]) * a.stride + gx[j]];
+    load_row(r + 2, w[d]);
     float v[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
@@ -1107,35 +1139,38 @@ __device__ inline void finish_strip(const FinishArgs& a, const float* __restrict
       const float cn = (w[u][c][0] + w[u][c][2]) + (w[d][c][0] + w[d][c][2]);
       v[c] = fmaf(a.k0[c], w[m][c][1], fmaf(a.k1[c], e4, a.k2[c] * cn));
     }
-    finish_store1(a, v, o0, o1, o2, ob + size_t(r) * a.out_stride, thr);
+    store(r, v);
   }
 }
 
 // One 64x32 tile; thread = one column of a ROWS-row strip (x0 + tid % 64,
 // rows y0 + ROWS (tid / 64) ..), so each row of a wave is one coalesced
-// load per channel and neighbour column.  Indices go through the 6.5
-// mirroring only in tiles that touch the frame edge.
+// load per channel and neighbour column.  Only tiles that touch the frame
+// edge take the mirrored indexing.  The 8-bit code thresholds are staged in
+// LDS; the 16-bit ones (256 KB) are read through the cache.
 template <int ROWS>
 __device__ __attribute__((always_inline)) inline void finish_tile(const FinishArgs& a, int tbx, int tby) {
   __shared__ float s_thr[257];
   const int tid = threadIdx.x;
   const int x0 = 64 * tbx, y0 = 32 * tby;
-  const float* thr = a.thr;
   if (a.format == JXLR_OUT_U8_SRGB) {
     for (int i = tid; i < 257; i += fin_threads<ROWS>()) s_thr[i] = a.thr[i];
     __syncthreads();
-    thr = s_thr;
   }
   const int x = x0 + (tid & 63), ys = y0 + ROWS * (tid >> 6);
   if (x >= a.W || ys >= a.H) return;
   const bool edge = x0 == 0 || x0 + 65 > a.W || y0 == 0 || y0 + 33 > a.H;
-  int gx[3], gy[ROWS + 2];
-#pragma unroll
-  for (int j = 0; j < 3; ++j) gx[j] = edge ? mirror(x - 1 + j, a.W) : x - 1 + j;
-#pragma unroll
-  for (int r = 0; r < ROWS + 2; ++r) gy[r] = edge ? mirror(ys - 1 + r, a.H) : ys - 1 + r;
-  finish_strip<ROWS>(a, a.in, a.out[0], a.out[1], a.out[2], thr, x, gx, gy, ys,
-                     min(ROWS, a.H - ys));
+  const int nrows = min(ROWS, a.H - ys);
+#define JXLR_FINISH(FMT, THR)                                                                    \
+  (edge ? finish_strip<ROWS, FMT, true>(a, a.in, a.out[0], a.out[1], a.out[2], THR, x, ys, nrows) \
+        : finish_strip<ROWS, FMT, false>(a, a.in, a.out[0], a.out[1], a.out[2], THR, x, ys, nrows))
+  if (a.format == JXLR_OUT_F32)
+    JXLR_FINISH(JXLR_OUT_F32, nullptr);
+  else if (a.format == JXLR_OUT_U8_SRGB)
+    JXLR_FINISH(JXLR_OUT_U8_SRGB, s_thr);
+  else
+    JXLR_FINISH(JXLR_OUT_U16_SRGB, a.thr);
+#undef JXLR_FINISH
 }
 
 // ---------------------------------------------------------------------------
