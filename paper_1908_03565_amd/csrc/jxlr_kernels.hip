@@ -31,6 +31,8 @@
 #include "jxlr_tables.h"
 
 using jxlr::DeviceTables;
+using jxlr::kSrgbBucket0;
+using jxlr::kSrgbBucketsPadded;
 
 struct jxlr_ctx {
   int device;
@@ -1007,6 +1009,7 @@ struct FinishArgs {
   void* out[3];
   size_t out_stride;
   const float* thr;  // decision thresholds of the 8- or 16-bit code
+  const uint8_t* start8;  // 8-bit code of each binary32 bucket
 };
 
 // sRGB transfer function of the clamped value, as an estimate: the power
@@ -1030,6 +1033,18 @@ __device__ inline int srgb_code(float v, const float* __restrict__ thr, int maxv
   return c;
 }
 
+// 8-bit output code of a linear sample, identical to the binary64
+// definition: the bucket of the clamped value's bit pattern (exponent and
+// top 7 mantissa bits) gives the code of the bucket's smallest value, and
+// since no bucket spans more than two codes one threshold settles the rest.
+__device__ inline int srgb_code8(float v, const float* __restrict__ thr,
+                                 const uint8_t* __restrict__ start) {
+  v = fminf(fmaxf(v, 0.0f), 1.0f);
+  const int b = max(int(__float_as_uint(v) >> 16) - kSrgbBucket0, 0);
+  const int c = start[b];
+  return c + (v >= thr[c + 1] ? 1 : 0);
+}
+
 // XYB -> RGB (L.2) of one pixel (v: X, Y, B after Gaborish).
 __device__ inline void xyb_to_rgb(const FinishArgs& a, const float (&v)[3], float (&rgb)[3]) {
   const float gr = v[1] + v[0], gg = v[1] - v[0], gb = v[2];
@@ -1047,9 +1062,10 @@ template <> struct OutT<JXLR_OUT_U8_SRGB> { using T = uint8_t; };
 template <> struct OutT<JXLR_OUT_U16_SRGB> { using T = uint16_t; };
 
 template <int FMT>
-__device__ inline typename OutT<FMT>::T encode_out(float v, const float* __restrict__ thr) {
+__device__ inline typename OutT<FMT>::T encode_out(float v, const float* __restrict__ thr,
+                                                   const uint8_t* __restrict__ start8) {
   if constexpr (FMT == JXLR_OUT_F32) return v;
-  else if constexpr (FMT == JXLR_OUT_U8_SRGB) return uint8_t(srgb_code(v, thr, 255));
+  else if constexpr (FMT == JXLR_OUT_U8_SRGB) return uint8_t(srgb_code8(v, thr, start8));
   else return uint16_t(srgb_code(v, thr, 65535));
 }
 
@@ -1070,8 +1086,8 @@ constexpr int fin_threads() { return 64 * 32 / ROWS; }
 template <int ROWS, int FMT, bool EDGE>
 __device__ inline void finish_strip(const FinishArgs& a, const float* __restrict__ in,
                                     void* __restrict__ o0, void* __restrict__ o1,
-                                    void* __restrict__ o2, const float* __restrict__ thr, int x,
-                                    int ys, int nrows) {
+                                    void* __restrict__ o2, const float* __restrict__ thr,
+                                    const uint8_t* __restrict__ start8, int x, int ys, int nrows) {
   using T = typename OutT<FMT>::T;
   const size_t plane = size_t(a.H) * a.stride;
   T* out[3] = {static_cast<T*>(o0) + size_t(ys) * a.out_stride + x,
@@ -1081,7 +1097,7 @@ __device__ inline void finish_strip(const FinishArgs& a, const float* __restrict
     float rgb[3];
     xyb_to_rgb(a, v, rgb);
 #pragma unroll
-    for (int c = 0; c < 3; ++c) out[c][size_t(r) * a.out_stride] = encode_out<FMT>(rgb[c], thr);
+    for (int c = 0; c < 3; ++c) out[c][size_t(r) * a.out_stride] = encode_out<FMT>(rgb[c], thr, start8);
   };
   if (!a.gab) {
     const float* p = in + size_t(ys) * a.stride + x;
@@ -1146,30 +1162,36 @@ __device__ inline void finish_strip(const FinishArgs& a, const float* __restrict
 // One 64x32 tile; thread = one column of a ROWS-row strip (x0 + tid % 64,
 // rows y0 + ROWS (tid / 64) ..), so each row of a wave is one coalesced
 // load per channel and neighbour column.  Only tiles that touch the frame
-// edge take the mirrored indexing.  The 8-bit code thresholds are staged in
-// LDS; the 16-bit ones (256 KB) are read through the cache.
+// edge take the mirrored indexing.  The 8-bit code tables are staged in
+// LDS; the 16-bit thresholds (256 KB) are read through the cache.
 template <int ROWS>
 __device__ __attribute__((always_inline)) inline void finish_tile(const FinishArgs& a, int tbx, int tby) {
   __shared__ float s_thr[257];
+  __shared__ uint32_t s_start[kSrgbBucketsPadded / 4];
   const int tid = threadIdx.x;
   const int x0 = 64 * tbx, y0 = 32 * tby;
   if (a.format == JXLR_OUT_U8_SRGB) {
     for (int i = tid; i < 257; i += fin_threads<ROWS>()) s_thr[i] = a.thr[i];
+    for (int i = tid; i < kSrgbBucketsPadded / 4; i += fin_threads<ROWS>())
+      s_start[i] = reinterpret_cast<const uint32_t*>(a.start8)[i];
     __syncthreads();
   }
   const int x = x0 + (tid & 63), ys = y0 + ROWS * (tid >> 6);
   if (x >= a.W || ys >= a.H) return;
   const bool edge = x0 == 0 || x0 + 65 > a.W || y0 == 0 || y0 + 33 > a.H;
   const int nrows = min(ROWS, a.H - ys);
-#define JXLR_FINISH(FMT, THR)                                                                    \
-  (edge ? finish_strip<ROWS, FMT, true>(a, a.in, a.out[0], a.out[1], a.out[2], THR, x, ys, nrows) \
-        : finish_strip<ROWS, FMT, false>(a, a.in, a.out[0], a.out[1], a.out[2], THR, x, ys, nrows))
+  const uint8_t* start8 = reinterpret_cast<const uint8_t*>(s_start);
+#define JXLR_FINISH(FMT, THR, ST)                                                                 \
+  (edge ? finish_strip<ROWS, FMT, true>(a, a.in, a.out[0], a.out[1], a.out[2], THR, ST, x, ys,    \
+                                        nrows)                                                   \
+        : finish_strip<ROWS, FMT, false>(a, a.in, a.out[0], a.out[1], a.out[2], THR, ST, x, ys,   \
+                                         nrows))
   if (a.format == JXLR_OUT_F32)
-    JXLR_FINISH(JXLR_OUT_F32, nullptr);
+    JXLR_FINISH(JXLR_OUT_F32, nullptr, nullptr);
   else if (a.format == JXLR_OUT_U8_SRGB)
-    JXLR_FINISH(JXLR_OUT_U8_SRGB, s_thr);
+    JXLR_FINISH(JXLR_OUT_U8_SRGB, s_thr, start8);
   else
-    JXLR_FINISH(JXLR_OUT_U16_SRGB, a.thr);
+    JXLR_FINISH(JXLR_OUT_U16_SRGB, a.thr, nullptr);
 #undef JXLR_FINISH
 }
 
@@ -1667,6 +1689,7 @@ jxlr_status make_finish_args(jxlr_ctx* ctx, const jxlr_frame_params* p, const jx
   for (int c = 0; c < 3; ++c) a.out[c] = io->out[c];
   a.out_stride = io->out_stride;
   a.thr = p->out_format == JXLR_OUT_U16_SRGB ? ctx->tables->srgb_thr16 : ctx->tables->srgb_thr8;
+  a.start8 = ctx->tables->srgb_start8;
   *res = a;
   return JXLR_OK;
 }

@@ -258,6 +258,22 @@ void epf_mul_table(int sigma_shift, int32_t* table) {
   }
 }
 
+bool srgb_bucket_starts(uint8_t* start) {
+  std::memset(start, 0, kSrgbBucketsPadded);
+  for (int b = 0; b < kSrgbBuckets; ++b) {
+    // smallest and largest binary32 value of the bucket (bucket 0 from 0)
+    const uint32_t lo_bits = b == 0 ? 0u : uint32_t(kSrgbBucket0 + b) << 16;
+    const uint32_t hi_bits = b == kSrgbBuckets - 1 ? lo_bits : (uint32_t(kSrgbBucket0 + b + 1) << 16) - 1;
+    float lo, hi;
+    std::memcpy(&lo, &lo_bits, 4);
+    std::memcpy(&hi, &hi_bits, 4);
+    const int c0 = srgb_code_f64(8, lo), c1 = srgb_code_f64(8, hi);
+    if (c1 - c0 > 1) return false;
+    start[b] = uint8_t(c0);
+  }
+  return true;
+}
+
 int srgb_code_f64(int bits, float v) {
   // IEC 61966-2-1 encoding of the clamped linear value, then round half up
   const double maxv = double((1 << bits) - 1);
@@ -344,6 +360,7 @@ bool build_tables(DeviceTables* t) {
   build_mfma_operands(t);
   srgb_thresholds(8, t->srgb_thr8);
   srgb_thresholds(16, t->srgb_thr16);
+  if (!srgb_bucket_starts(t->srgb_start8)) return false;
   std::vector<double> dq(1024);
   for (int s = 0; s < kNumStrategies; ++s) {
     const int X = 8 * blocks_x(s), Y = 8 * blocks_y(s), sz = X * Y;

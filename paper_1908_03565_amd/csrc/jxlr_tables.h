@@ -23,6 +23,13 @@ inline int blocks_y(int s) {
 // Offsets (in floats) of the per-type dequantization matrices inside
 // DeviceTables::dq; channel c of type s starts at dq_offset(s) + c * bx * by.
 int dq_offset(int s);
+// Buckets of binary32 values for the 8-bit output code: bucket b holds the
+// values whose bit pattern shifted right by 16 (sign, exponent and the top 7
+// mantissa bits) is kSrgbBucket0 + b, from 2^-14 up to 1.0 (b = 0 also takes
+// every smaller value).
+constexpr int kSrgbBucket0 = (127 - 14) << 7;
+constexpr int kSrgbBuckets = (127 << 7) - kSrgbBucket0 + 1;
+constexpr int kSrgbBucketsPadded = (kSrgbBuckets + 3) & ~3;
 constexpr int kDqFloats = 3 * (4 * 64 + 256 + 1024 + 2 * 128 + 2 * 256 + 2 * 512);
 
 // Everything the kernels read that does not depend on the frame.  One
@@ -61,6 +68,10 @@ struct DeviceTables {
   // c with srgb_thrB[c] <= v < srgb_thrB[c + 1].
   float srgb_thr8[257];
   float srgb_thr16[65537];
+  // 8-bit code of the smallest value of each bucket (see kSrgbBucket0); no
+  // bucket spans more than two codes (checked when the table is built), so
+  // the code of v is start + (v >= srgb_thr8[start + 1]).
+  alignas(4) uint8_t srgb_start8[kSrgbBucketsPadded];
   // Split-precision transform operands: the plain DCT-III matrix of a
   // 32-sample region side made of 32 / N diagonal N-point blocks (m = 0, 1, 2
   // for N = 8, 16, 32), A[i][k] = cos(pi (2 (i mod N) + 1)(k mod N) / (2 N))
@@ -86,6 +97,8 @@ void epf_mul_table(int sigma_shift, int32_t* table);
 int srgb_code_f64(int bits, float v);
 // Fills thr[0 .. 2^bits] as described for DeviceTables::srgb_thr8/16.
 void srgb_thresholds(int bits, float* thr);
+// Fills DeviceTables::srgb_start8; false if a bucket spans more than two codes.
+bool srgb_bucket_starts(uint8_t* start);
 // bfloat16 bit pattern of v rounded to nearest, ties to even.
 uint16_t bf16_rne(float v);
 

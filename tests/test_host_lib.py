@@ -126,6 +126,7 @@ def shim(tmp_path_factory):
     L.shim_mul.restype = C.POINTER(C.c_int32)
     L.shim_thr.restype = C.POINTER(C.c_float)
     L.shim_mfma.restype = C.POINTER(C.c_uint16)
+    L.shim_start8.restype = C.POINTER(C.c_uint8)
     assert L.shim_build() == 1
     return L
 
@@ -238,6 +239,33 @@ def test_srgb_thresholds_match_oracle_rounding(shim, bits):
     assert np.all(np.diff(t) > 0)
     np.testing.assert_array_equal(O.quantize_srgb(bits, t.astype(np.float64)), k)
     np.testing.assert_array_equal(O.quantize_srgb(bits, below.astype(np.float64)), k - 1)
+
+
+def test_srgb_8bit_bucket_code_is_oracle_rounding(shim):
+    # the kernel's 8-bit code (bucket of the clamped value's bit pattern, then
+    # one threshold) equals the oracle's rounding over a dense sweep of binary32
+    # values in and around [0, 1], every bucket boundary and every threshold
+    B0, nb = shim.shim_bucket0(), shim.shim_buckets()
+    start = _arr(shim.shim_start8(), nb).astype(np.int64)
+    thr = _arr(shim.shim_thr(8), 257).astype(np.float32)
+
+    def code8(v):
+        v = np.asarray(v, np.float32)
+        c = np.fmin(np.fmax(v, np.float32(0)), np.float32(1))  # as fminf / fmaxf
+        b = np.maximum((c.view(np.uint32) >> 16).astype(np.int64) - B0, 0)
+        s = start[b]
+        return s + (c >= thr[s + 1])
+
+    sweep = np.arange(0, 0x3F800001, 997, dtype=np.uint32).view(np.float32)
+    edges = (np.arange(B0, B0 + nb, dtype=np.uint32) << 16).view(np.float32)
+    t = thr[1:-1]
+    vals = np.concatenate([sweep, edges, np.nextafter(edges, np.float32(-1)), t,
+                           np.nextafter(t, np.float32(-1)), np.nextafter(t, np.float32(2)),
+                           np.float32([-1.0, -0.0, 1.0, 1.5, 3e38, -np.inf, np.inf])])
+    ref = O.quantize_srgb(8, vals.astype(np.float64))
+    np.testing.assert_array_equal(code8(vals), ref)
+    # each bucket spans at most two codes, as the kernel relies on
+    assert np.all(np.diff(start) >= 0) and start[0] == 0 and start[-1] == 255
 
 
 @pytest.mark.parametrize("m", [0, 1, 2])
