@@ -744,6 +744,10 @@ struct EpfArgs {
 };
 
 constexpr int kEpfTW = 64, kEpfTH = 32;  // output tile
+// Output rows per EPF thread; a tile takes 64 * 32 / kEpfRows threads.
+constexpr int kEpfRows = 4;
+constexpr int kEpfThreads = kEpfTW * kEpfTH / kEpfRows;
+constexpr int kEpfMinBlocks = 2;
 constexpr int kInW = 72, kInH = 38;      // s_in: columns x0-3.., rows y0-3..
 constexpr int kPW = 72, kPH = 40;        // s_p: start columns x0-4.., rows y0-4..
 constexpr int kGW = 19;                  // packed guide words per row: columns x0-4..x0+71
@@ -778,7 +782,7 @@ __device__ __attribute__((always_inline)) inline void epf_tile(const EpfArgs& a,
   // stride that keeps 16-byte alignment, load four columns at once.
   const bool interior = x0 >= 4 && x0 + 4 * kGW - 4 <= a.W && y0 >= 4 && y0 + kPH - 4 <= a.H;
   const bool vec = interior && (a.stride & 3) == 0 && (reinterpret_cast<uintptr_t>(a.in) & 15) == 0;
-  for (int it = tid; it < kPH * kGW; it += kThreads) {
+  for (int it = tid; it < kPH * kGW; it += kEpfThreads) {
     const int v = it / kGW, g = it % kGW;
     const int gy = interior ? y0 - 4 + v : mirror(y0 - 4 + v, a.H);
     float vals[3][4];
@@ -825,7 +829,7 @@ __device__ __attribute__((always_inline)) inline void epf_tile(const EpfArgs& a,
   __syncthreads();
 
   // B: guide words at every start column (four per aligned word pair).
-  for (int it = tid; it < 3 * kPH * (kGW - 1); it += kThreads) {
+  for (int it = tid; it < 3 * kPH * (kGW - 1); it += kEpfThreads) {
     const int c = it / (kPH * (kGW - 1));
     const int rem = it - c * (kPH * (kGW - 1));
     const int v = rem / (kGW - 1), g = rem - v * (kGW - 1);
@@ -839,7 +843,8 @@ __device__ __attribute__((always_inline)) inline void epf_tile(const EpfArgs& a,
   if (tid < 32) load_tile_info(a.info, a.Wb, a.Hb, gbx0, gby0, tid, s_strat, s_owner, s_bad);
   // Per-block range of `scaled` (J.2.4) over the block's pixels inside the
   // frame: eight lanes per block, one row each, reduced across the lanes.
-  {
+  static_assert(kEpfThreads >= 256, "range step needs 256 threads");
+  if (tid < 256) {
     const int b = tid >> 3, r = tid & 7;
     const int bxl = b & 7, byl = b >> 3;
     const int gy = y0 + 8 * byl + r;
@@ -902,35 +907,36 @@ __device__ __attribute__((always_inline)) inline void epf_tile(const EpfArgs& a,
   }
   __syncthreads();
 
-  // E: the strip of 8 pixels of column x.
-  const int lx = tid & 63, strip = tid >> 6;
-  const int x = x0 + lx, ys = y0 + 8 * strip;
+  // E: the strip of kEpfRows pixels of column x.
+  constexpr int R = kEpfRows;
+  const int lx = tid & 63, row0 = R * (tid >> 6);
+  const int x = x0 + lx, ys = y0 + row0;
   if (x >= a.W || ys >= a.H) return;
-  const int nrows = min(8, a.H - ys);
-  const int mul64 = s_mul[strip * 8 + (lx >> 3)];
+  const int nrows = min(R, a.H - ys);
+  const int bi = (row0 >> 3) * 8 + (lx >> 3);  // the pixel's block in the tile
+  const int mul64 = s_mul[bi];
   float* o0 = a.out + size_t(ys) * a.stride + x;
   if (a.guide_dbg) {
     const int wg = (lx + 4) >> 2, sh = 8 * ((lx + 4) & 3);
     for (int i = 0; i < nrows; ++i)
       for (int c = 0; c < 3; ++c)
-        a.guide_dbg[(size_t(c) * a.H + ys + i) * a.W + x] =
-            uint8_t(s_w[c][8 * strip + 4 + i][wg] >> sh);
+        a.guide_dbg[(size_t(c) * a.H + ys + i) * a.W + x] = uint8_t(s_w[c][row0 + 4 + i][wg] >> sh);
   }
   if (mul64 > 0) {  // sigma < 16: the pass leaves the pixel unchanged
     for (int i = 0; i < nrows; ++i)
       for (int c = 0; c < 3; ++c)
-        o0[c * plane + size_t(i) * a.stride] = s_in[c][8 * strip + 3 + i][lx + 3];
+        o0[c * plane + size_t(i) * a.stride] = s_in[c][row0 + 3 + i][lx + 3];
     return;
   }
-  const uint32_t thr = a.thr, smax = s_sadmax[strip * 8 + (lx >> 3)];
-  uint32_t ref[10][3];
+  const uint32_t thr = a.thr, smax = s_sadmax[bi];
+  uint32_t ref[R + 2][3];
 #pragma unroll
-  for (int j = 0; j < 10; ++j)
+  for (int j = 0; j < R + 2; ++j)
 #pragma unroll
-    for (int c = 0; c < 3; ++c) ref[j][c] = s_p[c][8 * strip + 3 + j][lx + 3];
-  float acc[8][4];
+    for (int c = 0; c < 3; ++c) ref[j][c] = s_p[c][row0 + 3 + j][lx + 3];
+  float acc[R][4];
 #pragma unroll
-  for (int i = 0; i < 8; ++i)
+  for (int i = 0; i < R; ++i)
 #pragma unroll
     for (int c = 0; c < 4; ++c) acc[i][c] = 0.0f;
 
@@ -941,27 +947,27 @@ __device__ __attribute__((always_inline)) inline void epf_tile(const EpfArgs& a,
   auto accumulate = [&](auto clamp_tag) {
     constexpr bool CLAMP = decltype(clamp_tag)::value;
     for (int cx = -3; cx <= 4; ++cx) {
-      uint32_t nb[16][3];
-      float inp[14][3];
+      uint32_t nb[R + 8][3];
+      float inp[R + 6][3];
 #pragma unroll
-      for (int j = 0; j < 16; ++j)
+      for (int j = 0; j < R + 8; ++j)
 #pragma unroll
-        for (int c = 0; c < 3; ++c) nb[j][c] = s_p[c][8 * strip + j][lx + 3 + cx];
+        for (int c = 0; c < 3; ++c) nb[j][c] = s_p[c][row0 + j][lx + 3 + cx];
 #pragma unroll
-      for (int j = 0; j < 14; ++j)
+      for (int j = 0; j < R + 6; ++j)
 #pragma unroll
-        for (int c = 0; c < 3; ++c) inp[j][c] = s_in[c][8 * strip + j][lx + 3 + cx];
+        for (int c = 0; c < 3; ++c) inp[j][c] = s_in[c][row0 + j][lx + 3 + cx];
 #pragma unroll
       for (int cy = -3; cy <= 3; ++cy) {
-        uint32_t rs[10];
+        uint32_t rs[R + 2];
 #pragma unroll
-        for (int j = 0; j < 10; ++j) {
+        for (int j = 0; j < R + 2; ++j) {
           uint32_t s = __builtin_amdgcn_sad_u8(ref[j][0], nb[j + cy + 3][0], 0u);
           s = __builtin_amdgcn_sad_u8(ref[j][1], nb[j + cy + 3][1], s);
           rs[j] = __builtin_amdgcn_sad_u8(ref[j][2], nb[j + cy + 3][2], s);
         }
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
+        for (int i = 0; i < R; ++i) {
           const uint32_t sad = add3(rs[i], rs[i + 1], rs[i + 2]);
           uint32_t wb;
           if constexpr (CLAMP) {
@@ -985,7 +991,7 @@ __device__ __attribute__((always_inline)) inline void epf_tile(const EpfArgs& a,
   else
     accumulate(std::false_type{});
 #pragma unroll
-  for (int i = 0; i < 8; ++i)
+  for (int i = 0; i < R; ++i)
     if (i < nrows)
 #pragma unroll
       for (int c = 0; c < 3; ++c)
@@ -1225,7 +1231,7 @@ __global__ __launch_bounds__(kRecThreads, kRecMinBlocks) void recon_kernel(Recon
   const int t = xcd_tile(blockIdx.x, gridDim.x);
   recon_tile(a, t % tiles_x, t / tiles_x);
 }
-__global__ __launch_bounds__(kThreads, 2) void epf_kernel(EpfArgs a, int tiles_x) {
+__global__ __launch_bounds__(kEpfThreads, kEpfMinBlocks) void epf_kernel(EpfArgs a, int tiles_x) {
   const int t = xcd_tile(blockIdx.x, gridDim.x);
   epf_tile(a, t % tiles_x, t / tiles_x);
 }
@@ -1329,7 +1335,7 @@ __global__ __launch_bounds__(kRecThreads) void recon_batch_kernel(BatchArgs b) {
 }
 
 template <bool PERSIST>
-__global__ __launch_bounds__(kThreads, 2) void epf_batch_kernel(BatchArgs b) {
+__global__ __launch_bounds__(kEpfThreads, kEpfMinBlocks) void epf_batch_kernel(BatchArgs b) {
   for (TileRange r(b.order, b.tile_start[b.n]); r.t < r.end; r.t += r.step) {
     if (PERSIST) __syncthreads();
     const int f = __builtin_amdgcn_readfirstlane(b.tile_frame[r.t]);
@@ -1739,7 +1745,7 @@ jxlr_status jxlr_epf_pass(jxlr_ctx* ctx, const jxlr_frame_params* p, const jxlr_
   if (st) return st;
   DeviceGuard g(ctx->device);
   if (!g.ok) return JXLR_E_HIP;
-  hipLaunchKernelGGL(epf_kernel, dim3(tiles_x(p) * tiles_y(p)), dim3(kThreads), 0, stream, a,
+  hipLaunchKernelGGL(epf_kernel, dim3(tiles_x(p) * tiles_y(p)), dim3(kEpfThreads), 0, stream, a,
                      tiles_x(p));
   return launch_status(hipGetLastError());
 }
@@ -1847,9 +1853,9 @@ jxlr_status launch_stage(jxlr_ctx* ctx, const jxlr_batch_plan* plan, int stage, 
       break;
     case JXLR_STAGE_EPF:
       if (persist)
-        hipLaunchKernelGGL(epf_batch_kernel<true>, dim3(gsz), dim3(kThreads), 0, stream, b);
+        hipLaunchKernelGGL(epf_batch_kernel<true>, dim3(gsz), dim3(kEpfThreads), 0, stream, b);
       else
-        hipLaunchKernelGGL(epf_batch_kernel<false>, dim3(gsz), dim3(kThreads), 0, stream, b);
+        hipLaunchKernelGGL(epf_batch_kernel<false>, dim3(gsz), dim3(kEpfThreads), 0, stream, b);
       break;
     case JXLR_STAGE_FINISH:
       if (persist)
@@ -1997,7 +2003,7 @@ jxlr_status jxlr_autotune(jxlr_ctx* ctx, const jxlr_batch_plan* plan, int reps,
   const void* kerns[3] = {reinterpret_cast<const void*>(recon_batch_kernel<true>),
                           reinterpret_cast<const void*>(epf_batch_kernel<true>),
                           reinterpret_cast<const void*>(finish_batch_kernel<true>)};
-  const int threads[3] = {kRecThreads, kThreads, fin_threads<kFinRowsBatch>()};
+  const int threads[3] = {kRecThreads, kEpfThreads, fin_threads<kFinRowsBatch>()};
   jxlr_launch_config out{};
   float total_ms = 0.0f;
   for (int si = 0; si < 3 && !st; ++si) {
