@@ -33,9 +33,12 @@ sys.path.insert(0, ROOT)
 
 # Peaks of one MI355X used for the roofline fractions.
 HBM_PEAK_GBS = 8000.0
-# Plain 32-bit VALU issue: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz (one op per
-# lane per clock, FMA counted once).
-ALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+# Plain 32-bit VALU issue: the fp32 vector peak of 157.3 TFLOP/s with an FMA
+# counted as one op, i.e. 256 CUs x 4 SIMD x 32 lanes x 2.4 GHz (two wave64
+# instructions per CU per clock).  Simple ops (adds, logic, FMA) issue at
+# this rate; the packed-byte SAD, three-input adds and 24-bit multiplies at
+# half of it.
+ALU_PEAK_TOPS = 256 * 4 * 32 * 2.4e9 / 1e12
 # Algorithmic work per pixel of one EPF pass (separable formulation): for each
 # of the 56 window offsets, one packed 3-channel SAD of the new sample pair,
 # 3 + 2 adds of the 4x3 patch box sum, 6 ops of Weight and the threshold,
@@ -179,6 +182,33 @@ def bench_frame(args, J, wl, torch, np):
                            p.out_format, ("recon_kernel", "epf_kernel", "finish_kernel"))
     roofline = roofline_of(kernels, {"epf_kernel": n_epf}, frame["name"], W * H)
 
+    graph_lat = None
+    if args.workload == "c1":
+        # single-frame latency without per-stage events: the frame as a batch
+        # of one, its four kernels replayed from a captured graph
+        pb = J.params(W, H, out_format=frame["out_format"], idct_split=int(args.split),
+                      **frame["params"])
+        gout = ctx.empty_out(pb)
+        plan = ctx.batch_prepare([pb], [df.io(gout)], ctx.batch_workspace([pb]))
+        g = ctx.graph(plan)
+        for _ in range(20):
+            g.launch(stream)
+        torch.cuda.synchronize()
+        gev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(200)]
+        for a, b in gev:
+            a.record(stream)
+            g.launch(stream)
+            b.record(stream)
+        torch.cuda.synchronize()
+        gl = [a.elapsed_time(b) for a, b in gev]
+        assert torch.equal(gout, out), "graph replay differs from the stage-by-stage decode"
+        graph_lat = {"p50": round(float(np.percentile(gl, 50)), 5),
+                     "p99": round(float(np.percentile(gl, 99)), 5)}
+        log(f"bench: single-frame graph latency p50 {graph_lat['p50']:.4f} ms, "
+            f"p99 {graph_lat['p99']:.4f} ms")
+        g.close()
+
     err = None
     cpu = None
     if not args.no_check or not args.no_cpu_baseline:
@@ -222,6 +252,7 @@ def bench_frame(args, J, wl, torch, np):
                    else "f32"},
         "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 5),
                        "p99": round(float(np.percentile(lat, 99)), 5)},
+        "graph_latency_ms": graph_lat,
         "stage_ms": {"reconstruct": round(recon_ms, 5), "epf": [round(x, 5) for x in epf_ms],
                      "finish": round(fin_ms, 5)},
         "host_wall_ms_per_step": round(wall / args.steps * 1e3, 5),
