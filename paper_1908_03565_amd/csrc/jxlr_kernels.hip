@@ -748,7 +748,7 @@ constexpr int kEpfTW = 64, kEpfTH = 32;  // output tile
 constexpr int kEpfRows = 4;
 constexpr int kEpfThreads = kEpfTW * kEpfTH / kEpfRows;
 constexpr int kEpfMinBlocks = 2;
-constexpr int kInW = 72, kInH = 38;      // s_in: columns x0-3.., rows y0-3..
+constexpr int kInW = 72, kInH = 38;      // s_in: columns x0-4.., rows y0-3..
 constexpr int kPW = 72, kPH = 40;        // s_p: start columns x0-4.., rows y0-4..
 constexpr int kGW = 19;                  // packed guide words per row: columns x0-4..x0+71
 
@@ -762,8 +762,10 @@ __device__ inline uint32_t guide_byte(float v, float minv, float scale) {
 // One 64x32 output tile of an EPF pass.  Threads may return after the last
 // barrier.
 __device__ __attribute__((always_inline)) inline void epf_tile(const EpfArgs& a, int tbx, int tby) {
-  __shared__ float s_in[3][kInH][kInW];
-  __shared__ uint32_t s_p[3][kPH][kPW];
+  // 16-byte aligned rows (72 words): stage A and B store four words at once
+  __shared__ __attribute__((aligned(16))) float s_in[3][kInH][kInW];
+  __shared__ __attribute__((aligned(16))) uint32_t s_p[3][kPH][kPW];
+  static_assert(kInW % 4 == 0 && kPW % 4 == 0, "16-byte rows");
   __shared__ uint32_t s_w[3][kPH][kGW + 1];
   __shared__ float s_rng[32];
   __shared__ int s_mul[32];
@@ -813,15 +815,14 @@ __device__ __attribute__((always_inline)) inline void epf_tile(const EpfArgs& a,
       for (int j = 0; j < 4; ++j) w |= guide_byte(vals[c][j], a.minv[c], a.scale[c]) << (8 * j);
       s_w[c][v][g] = w;
     }
+    // the four samples as one 16-byte store per channel (s_in columns start
+    // at x0 - 4 like the words)
     const int ri = v - 1;
-    if (ri >= 0 && ri < kInH) {
+    if (ri >= 0 && ri < kInH && 4 * g < kInW) {
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int ci = 4 * g + j - 1;
-        if (ci >= 0 && ci < kInW)
-#pragma unroll
-          for (int c = 0; c < 3; ++c) s_in[c][ri][ci] = vals[c][j];
-      }
+      for (int c = 0; c < 3; ++c)
+        *reinterpret_cast<float4*>(&s_in[c][ri][4 * g]) =
+            make_float4(vals[c][0], vals[c][1], vals[c][2], vals[c][3]);
     }
   }
   if (tid < 2) s_bad[tid] = 0;
@@ -834,27 +835,26 @@ __device__ __attribute__((always_inline)) inline void epf_tile(const EpfArgs& a,
     const int rem = it - c * (kPH * (kGW - 1));
     const int v = rem / (kGW - 1), g = rem - v * (kGW - 1);
     const uint32_t lo = s_w[c][v][g], hi = s_w[c][v][g + 1];
-    uint32_t* dst = &s_p[c][v][4 * g];
-    dst[0] = lo;
-    dst[1] = __builtin_amdgcn_alignbyte(hi, lo, 1);
-    dst[2] = __builtin_amdgcn_alignbyte(hi, lo, 2);
-    if (4 * g + 3 < kPW - 1) dst[3] = __builtin_amdgcn_alignbyte(hi, lo, 3);
+    // one 16-byte store (the last word of the row is never read)
+    *reinterpret_cast<uint4*>(&s_p[c][v][4 * g]) =
+        make_uint4(lo, __builtin_amdgcn_alignbyte(hi, lo, 1), __builtin_amdgcn_alignbyte(hi, lo, 2),
+                   __builtin_amdgcn_alignbyte(hi, lo, 3));
   }
   if (tid < 32) load_tile_info(a.info, a.Wb, a.Hb, gbx0, gby0, tid, s_strat, s_owner, s_bad);
   // Per-block range of `scaled` (J.2.4) over the block's pixels inside the
-  // frame: eight lanes per block, one row each, reduced across the lanes.
+  // frame: eight lanes per block, one column each (a wave reads whole tile
+  // rows, free of bank conflicts), reduced across the lanes.
   static_assert(kEpfThreads >= 256, "range step needs 256 threads");
   if (tid < 256) {
-    const int b = tid >> 3, r = tid & 7;
+    const int b = tid >> 3, j = tid & 7;
     const int bxl = b & 7, byl = b >> 3;
-    const int gy = y0 + 8 * byl + r;
     float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-    if (gy < a.H)
-      for (int j = 0; j < 8; ++j) {
-        if (x0 + 8 * bxl + j >= a.W) break;
+    if (x0 + 8 * bxl + j < a.W)
+      for (int r = 0; r < 8; ++r) {
+        if (y0 + 8 * byl + r >= a.H) break;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-          const float sc = (s_in[c][3 + 8 * byl + r][3 + 8 * bxl + j] - a.minv[c]) * a.scale[c];
+          const float sc = (s_in[c][3 + 8 * byl + r][4 + 8 * bxl + j] - a.minv[c]) * a.scale[c];
           lo[c] = fminf(lo[c], sc);
           hi[c] = fmaxf(hi[c], sc);
         }
@@ -868,7 +868,7 @@ __device__ __attribute__((always_inline)) inline void epf_tile(const EpfArgs& a,
       }
       if (hi[c] >= lo[c]) rg = fmaxf(rg, hi[c] - lo[c]);
     }
-    if (r == 0) s_rng[b] = rg;
+    if (j == 0) s_rng[b] = rg;
   }
   __syncthreads();
 
@@ -925,7 +925,7 @@ __device__ __attribute__((always_inline)) inline void epf_tile(const EpfArgs& a,
   if (mul64 > 0) {  // sigma < 16: the pass leaves the pixel unchanged
     for (int i = 0; i < nrows; ++i)
       for (int c = 0; c < 3; ++c)
-        o0[c * plane + size_t(i) * a.stride] = s_in[c][row0 + 3 + i][lx + 3];
+        o0[c * plane + size_t(i) * a.stride] = s_in[c][row0 + 3 + i][lx + 4];
     return;
   }
   const uint32_t thr = a.thr, smax = s_sadmax[bi];
@@ -956,7 +956,7 @@ __device__ __attribute__((always_inline)) inline void epf_tile(const EpfArgs& a,
 #pragma unroll
       for (int j = 0; j < R + 6; ++j)
 #pragma unroll
-        for (int c = 0; c < 3; ++c) inp[j][c] = s_in[c][row0 + j][lx + 3 + cx];
+        for (int c = 0; c < 3; ++c) inp[j][c] = s_in[c][row0 + j][lx + 4 + cx];
 #pragma unroll
       for (int cy = -3; cy <= 3; ++cy) {
         uint32_t rs[R + 2];
