@@ -66,16 +66,20 @@ def log(msg):
 PMC_COPY_SCALE = {"FETCH_SIZE": 2.0, "WRITE_SIZE": 1.0}
 PMC_SOURCES = ("paper_1908_03565_amd/csrc/jxlr_kernels.hip", "paper_1908_03565_amd/csrc/jxlr_tables.cpp",
                "paper_1908_03565_amd/csrc/jxlr_tables.h", "paper_1908_03565_amd/csrc/gen_dct_consts.py")
-PMC_SOURCES_SHA256 = "b62b14fadaa2c7e789cf539b0d8e3510a9956233facd3be7f529ac2cd539418c"
+PMC_SOURCES_SHA256 = "d47e408e0a8237f0918f209b0d90aa444c1591597e2a1a4e634f84eb844d6ea8"
 # (workload name, kernel) -> (FETCH_SIZE KiB, WRITE_SIZE KiB) per dispatch
 PMC_KIB = {
-    ("c2_2048x2048_mixed_epf2", "epf_kernel"): (25479.3, 49152.0),
-    ("c2_2048x2048_mixed_epf2", "recon_kernel"): (25470.8, 49152.0),
-    ("c2_2048x2048_mixed_epf2", "finish_kernel"): (24849.0, 49152.0),
-    ("c3_4096x4096_half_dct32", "epf_kernel"): (101210.3, 196608.2),
-    ("c4_batch64_loguniform_256_3072_epf1_u8srgb", "epf_batch_kernel"): (1099745.9, 1051484.5),
-    ("c1x1024_256x256_dct8", "recon_batch_kernel"): (427036.9, 786442.4),
-    ("c1x1024_256x256_dct8", "finish_batch_kernel"): (850215.8, 786432.0),
+    ("c2_2048x2048_mixed_epf2", "epf_kernel"): (25446.9, 49152.0),
+    ("c2_2048x2048_mixed_epf2", "recon_kernel"): (25627.3, 49316.6),
+    ("c2_2048x2048_mixed_epf2", "finish_kernel"): (24913.0, 49152.0),
+    ("c3_4096x4096_half_dct32", "epf_kernel"): (100135.1, 196608.0),
+    ("c3_4096x4096_half_dct32", "recon_kernel"): (100941.7, 196933.1),
+    ("c3_4096x4096_half_dct32", "finish_kernel"): (98929.8, 196608.0),
+    ("c4_batch64_loguniform_256_3072_epf1_u8srgb", "epf_batch_kernel"): (528694.4, 1052226.5),
+    ("c4_batch64_loguniform_256_3072_epf1_u8srgb", "recon_batch_kernel"): (536272.2, 1061301.2),
+    ("c4_batch64_loguniform_256_3072_epf1_u8srgb", "finish_batch_kernel"): (526389.8, 263635.6),
+    ("c1x1024_256x256_dct8", "recon_batch_kernel"): (401006.3, 786433.6),
+    ("c1x1024_256x256_dct8", "finish_batch_kernel"): (845161.7, 786432.0),
 }
 
 
@@ -219,8 +223,17 @@ def bench_frame(args, J, wl, torch, np):
         t = time.perf_counter()
         orc = O.decode_stages(q, frame)
         cpu_s = time.perf_counter() - t
-        cpu = dict(value=round(mp / cpu_s, 4), unit="MP/s", cores=O.num_threads(), kind="oracle",
-                   sample=f"one full {W}x{H} decode ({cpu_s:.2f} s), FP64 scalar C, OpenMP")
+        reps = 1
+        if not args.no_cpu_baseline:
+            # repeat the whole decode until about args.cpu_seconds of host work
+            while cpu_s < args.cpu_seconds and reps < 100000:
+                t = time.perf_counter()
+                O.decode(q, frame)
+                cpu_s += time.perf_counter() - t
+                reps += 1
+        cpu = dict(value=round(mp * reps / cpu_s, 4), unit="MP/s", cores=O.num_threads(),
+                   kind="oracle",
+                   sample=f"{reps} full {W}x{H} decode(s) in {cpu_s:.2f} s, FP64 scalar C, OpenMP")
         if not args.no_check:
             gpu = P.gpu_stages(ctx, p, df)
             np.testing.assert_array_equal(gpu["out"], out.cpu().numpy())
@@ -296,7 +309,7 @@ def bench_batch(args, J, wl, torch, np):
         f"workspace {ws.numel() / 2**30:.2f} GiB")
     cfg, tinfo = tuning.tuned_config(ctx, plan, stream=stream, retune=args.retune)
     log(f"bench: schedule {cfg.as_dict()} ({'cached' if tinfo['cached'] else 'tuned'}, "
-        f"{tinfo['tuned_ms']} ms)")
+        f"{tinfo['tuned_ms']} ms; key {tinfo['key']})")
     graph = ctx.graph(plan, cfg)
     for _ in range(args.warmup):
         graph.launch(stream)

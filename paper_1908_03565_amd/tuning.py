@@ -3,8 +3,9 @@
 jxlr_autotune (native) times the candidate workgroup counts and tile orders
 of each persistent stage kernel for one prepared batch.  The choice depends
 on the device and on the batch's shape (how many tiles, how many EPF passes),
-not on its pixel values, so it is cached under a key made of the device name,
-the tile count rounded to a power of two and the largest EPF pass count.
+not on its pixel values, so it is cached under a key made of the device
+(architecture and compute-unit count), the tile count rounded to a power of
+two and the largest EPF pass count.
 The cache is a JSON file at $JXLR_TUNE_CACHE, else ~/.cache/jxlr/schedules.json.
 """
 import json
@@ -46,7 +47,10 @@ def tuned_config(ctx, plan, stream=None, reps=5, path=None, retune=False):
     retune is set) and records the result."""
     import torch
     path = path or cache_path()
-    name = torch.cuda.get_device_name(ctx.device)
+    # the architecture and compute-unit count name the device (the marketing
+    # name can read differently under a profiler)
+    props = torch.cuda.get_device_properties(ctx.device)
+    name = f"{props.gcnArchName.split(':')[0]}x{props.multi_processor_count}"
     key = batch_key(name, plan)
     cache = _load(path)
     ent = cache.get(key)
