@@ -42,7 +42,9 @@ struct jxlr_ctx {
 
 namespace {
 
-constexpr int kThreads = 256;
+// Block-info threads per workgroup (one region each): small workgroups spread
+// the few regions of a frame over many compute units.
+constexpr int kInfoThreads = 64;
 constexpr uint8_t kAbsent = 0xFF;
 
 // Varblock size in blocks of transform type s (I.2.5): "DCT N x M" is N wide.
@@ -107,8 +109,21 @@ __device__ inline void blockinfo_region(const InfoArgs& a, int rid) {
     raw[i] = (bx < nbx && by < nby) ? a.strategy[size_t(gby0 + by) * a.map_stride + gbx0 + bx] : 0u;
     info[i] = kInvalid;
   }
+  // A whole region whose 16 entries all name one type: the raster scan
+  // finds exactly that type's regular grid of varblocks, so it is written
+  // directly (every region of a frame drawn per region takes this path).
+  bool uni = nbx == 4 && nby == 4 && raw[0] < uint32_t(jxlr::kNumStrategies);
+#pragma unroll
+  for (int i = 1; i < 16; ++i) uni = uni && raw[i] == raw[0];
   uint32_t covered = 0;
   bool ok = true;
+  if (uni) {
+    const int s = int(raw[0]), cx = vb_bx(s), cy = vb_by(s);
+#pragma unroll
+    for (int j = 0; j < 16; ++j)
+      info[j] = uint32_t(s) | uint32_t((j & 3) % cx) << 4 | uint32_t((j >> 2) % cy) << 6;
+    covered = 0xFFFFu;
+  }
 #pragma unroll
   for (int i = 0; i < 16; ++i) {
     const int bx = i & 3, by = i >> 2;
@@ -1208,8 +1223,8 @@ __device__ __attribute__((always_inline)) inline void finish_tile(const FinishAr
 // loop, so a fixed, tunable grid serves any batch; the frame of a tile is
 // found by binary search over per-frame tile offsets.
 
-__global__ __launch_bounds__(kThreads) void blockinfo_kernel(InfoArgs a) {
-  blockinfo_region(a, blockIdx.x * kThreads + threadIdx.x);
+__global__ __launch_bounds__(kInfoThreads) void blockinfo_kernel(InfoArgs a) {
+  blockinfo_region(a, blockIdx.x * kInfoThreads + threadIdx.x);
 }
 // Workgroups are handed to the eight XCDs round-robin (workgroup b runs on
 // XCD b mod 8).  xcd_tile(b, G) renumbers the G workgroups of a launch so
@@ -1296,9 +1311,9 @@ struct TileRange {
   }
 };
 
-__global__ __launch_bounds__(kThreads) void blockinfo_batch_kernel(BatchArgs b) {
+__global__ __launch_bounds__(kInfoThreads) void blockinfo_batch_kernel(BatchArgs b) {
   const int total = b.region_start[b.n];
-  for (int rid = blockIdx.x * kThreads + threadIdx.x; rid < total; rid += gridDim.x * kThreads) {
+  for (int rid = blockIdx.x * kInfoThreads + threadIdx.x; rid < total; rid += gridDim.x * kInfoThreads) {
     const int f = find_frame(b.region_start, b.n, rid);
     blockinfo_region(b.frames[f].info, rid - b.region_start[f]);
   }
@@ -1718,7 +1733,7 @@ jxlr_status jxlr_block_info(jxlr_ctx* ctx, const jxlr_frame_params* p, const jxl
   DeviceGuard g(ctx->device);
   if (!g.ok) return JXLR_E_HIP;
   const int regions = regions_of(p);
-  hipLaunchKernelGGL(blockinfo_kernel, dim3((regions + kThreads - 1) / kThreads), dim3(kThreads), 0,
+  hipLaunchKernelGGL(blockinfo_kernel, dim3((regions + kInfoThreads - 1) / kInfoThreads), dim3(kInfoThreads), 0,
                      stream, a);
   return launch_status(hipGetLastError());
 }
@@ -1823,7 +1838,7 @@ jxlr_status check_plan(jxlr_ctx* ctx, const jxlr_batch_plan* plan) {
 }
 
 // Enqueues one stage of a prepared batch.  grid <= 0 picks one workgroup per
-// tile (per kThreads regions for the block-info stage); larger grids are
+// tile (per kInfoThreads regions for the block-info stage); larger grids are
 // clamped to that.
 jxlr_status launch_stage(jxlr_ctx* ctx, const jxlr_batch_plan* plan, int stage, int grid,
                          int order, int epf_pass, hipStream_t stream) {
@@ -1835,7 +1850,7 @@ jxlr_status launch_stage(jxlr_ctx* ctx, const jxlr_batch_plan* plan, int stage, 
   b.region_start = reinterpret_cast<const int*>(base + plan->region_start_offset);
   b.n = plan->n;
   b.pass = epf_pass;
-  const int full = stage == JXLR_STAGE_INFO ? (plan->total_regions + kThreads - 1) / kThreads
+  const int full = stage == JXLR_STAGE_INFO ? (plan->total_regions + kInfoThreads - 1) / kInfoThreads
                                             : plan->total_tiles;
   int gsz = grid > 0 ? std::min(grid, full) : full;
   b.order = order == 1 ? 1 : 0;
@@ -1843,7 +1858,7 @@ jxlr_status launch_stage(jxlr_ctx* ctx, const jxlr_batch_plan* plan, int stage, 
   const bool persist = gsz < full;
   switch (stage) {
     case JXLR_STAGE_INFO:
-      hipLaunchKernelGGL(blockinfo_batch_kernel, dim3(gsz), dim3(kThreads), 0, stream, b);
+      hipLaunchKernelGGL(blockinfo_batch_kernel, dim3(gsz), dim3(kInfoThreads), 0, stream, b);
       break;
     case JXLR_STAGE_RECON:
       if (persist)
