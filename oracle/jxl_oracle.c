@@ -98,8 +98,8 @@ int orc_varblock_size(int s, int32_t* bx, int32_t* by) {
   return 1;
 }
 
-/* Transform types this oracle reconstructs (DCT4x8, DCT8x4 and AFV are not). */
-static int supported(int s) { return s >= 0 && s <= 11; }
+/* Transform types this oracle reconstructs: every C.5.4 value. */
+static int supported(int s) { return s >= 0 && s <= 14; }
 
 static int is_dct_family(int s) {
   return s == ORC_DCT8 || (s >= ORC_DCT16 && s <= ORC_DCT16X32);
@@ -301,12 +301,151 @@ static void inv_identity(const double* K, double* S) {
     }
 }
 
+/* The 16 x 16 orthonormal AFV basis of I.2.2; a 4 x 4 block is a 16-vector
+ * with entry (x, y) at index 4 y + x.  Reading: two rows print 17 entries;
+ * row 4 loses a trailing zero and row 9 the zero at index 3, which makes the
+ * basis orthonormal (to 1.4e-14, tested). */
+static const double AFV_BASIS[16][16] = {
+    {0.25, 0.25, 0.25, 0.25, 0.25, 0.25, 0.25, 0.25, 0.25, 0.25, 0.25, 0.25, 0.25, 0.25, 0.25,
+     0.25},
+    {0.876902929799142, 0.2206518106944235, -0.10140050393753763, -0.1014005039375375,
+     0.2206518106944236, -0.10140050393753777, -0.10140050393753772, -0.10140050393753763,
+     -0.10140050393753758, -0.10140050393753769, -0.1014005039375375, -0.10140050393753768,
+     -0.10140050393753768, -0.10140050393753759, -0.10140050393753763, -0.10140050393753741},
+    {0.0, 0.0, 0.40670075830260755, 0.44444816619734445, 0.0, 0.0, 0.19574399372042936,
+     0.2929100136981264, -0.40670075830260716, -0.19574399372042872, 0.0, 0.11379074460448091,
+     -0.44444816619734384, -0.29291001369812636, -0.1137907446044814, 0.0},
+    {0.0, 0.0, -0.2125574805828748, 0.3085497062849767, 0.0, 0.4706702258572536,
+     -0.1621205195722993, 0.0, -0.21255748058287047, -0.16212051957228327, -0.47067022585725277,
+     -0.1464291867126764, 0.3085497062849487, 0.0, -0.1464291867126536, 0.4251149611657548},
+    {0.0, -0.7071067811865474, 0.0, 0.0, 0.7071067811865476, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0,
+     0.0, 0.0, 0.0, 0.0},
+    {-0.4105377591765233, 0.6235485373547691, -0.06435071657946274, -0.06435071657946266,
+     0.6235485373547694, -0.06435071657946284, -0.0643507165794628, -0.06435071657946274,
+     -0.06435071657946272, -0.06435071657946279, -0.06435071657946266, -0.06435071657946277,
+     -0.06435071657946277, -0.06435071657946273, -0.06435071657946274, -0.0643507165794626},
+    {0.0, 0.0, -0.4517556589999482, 0.15854503551840063, 0.0, -0.04038515160822202,
+     0.0074182263792423875, 0.39351034269210167, -0.45175565899994635, 0.007418226379244351,
+     0.1107416575309343, 0.08298163094882051, 0.15854503551839705, 0.3935103426921022,
+     0.0829816309488214, -0.45175565899994796},
+    {0.0, 0.0, -0.304684750724869, 0.5112616136591823, 0.0, 0.0, -0.290480129728998,
+     -0.06578701549142804, 0.304684750724884, 0.2904801297290076, 0.0, -0.23889773523344604,
+     -0.5112616136592012, 0.06578701549142545, 0.23889773523345467, 0.0},
+    {0.0, 0.0, 0.3017929516615495, 0.25792362796341184, 0.0, 0.16272340142866204,
+     0.09520022653475037, 0.0, 0.3017929516615503, 0.09520022653475055, -0.16272340142866173,
+     -0.35312385449816297, 0.25792362796341295, 0.0, -0.3531238544981624, -0.6035859033230976},
+    {0.0, 0.0, 0.40824829046386274, 0.0, 0.0, 0.0, 0.0, -0.4082482904638628, -0.4082482904638635,
+     0.0, 0.0, -0.40824829046386296, 0.0, 0.408248290463863, 0.408248290463863, 0.0},
+    {0.0, 0.0, 0.1747866975480809, 0.0812611176717539, 0.0, 0.0, -0.3675398009862027,
+     -0.307882213957909, -0.17478669754808135, 0.3675398009862011, 0.0, 0.4826689115059883,
+     -0.08126111767175039, 0.30788221395790305, -0.48266891150598584, 0.0},
+    {0.0, 0.0, -0.21105601049335784, 0.18567180916109802, 0.0, 0.0, 0.49215859013738733,
+     -0.38525013709251915, 0.21105601049335806, -0.49215859013738905, 0.0, 0.17419412659916217,
+     -0.18567180916109904, 0.3852501370925211, -0.1741941265991621, 0.0},
+    {0.0, 0.0, -0.14266084808807264, -0.3416446842253372, 0.0, 0.7367497537172237,
+     0.24627107722075148, -0.08574019035519306, -0.14266084808807344, 0.24627107722075137,
+     0.14883399227113567, -0.04768680350229251, -0.3416446842253373, -0.08574019035519267,
+     -0.047686803502292804, -0.14266084808807242},
+    {0.0, 0.0, -0.13813540350758585, 0.3302282550303788, 0.0, 0.08755115000587084,
+     -0.07946706605909573, -0.4613374887461511, -0.13813540350758294, -0.0794670660591026,
+     0.49724647109535086, 0.12538059448563663, 0.3302282550303805, -0.4613374887461554,
+     0.12538059448564315, -0.13813540350758452},
+    {0.0, 0.0, -0.1743760259965106, 0.0702790691196284, 0.0, -0.2921026642334881,
+     0.3623817333531167, 0.0, -0.1743760259965108, 0.36238173335311646, 0.29210266423348785,
+     -0.4326608024727445, 0.07027906911962818, 0.0, -0.4326608024727457, 0.34875205199302267},
+    {0.0, 0.0, 0.1135498731499337, -0.07417504595810355, 0.0, 0.19402893032594343,
+     -0.435190496523228, 0.21918684838857466, 0.11354987314994257, -0.4351904965232251,
+     0.5550443808910661, -0.25468277124066463, -0.07417504595810233, 0.2191868483885728,
+     -0.25468277124066413, 0.1135498731499429},
+};
+
+void orc_afv_basis(double* out) {
+  for (int i = 0; i < 16; ++i)
+    for (int j = 0; j < 16; ++j) out[i * 16 + j] = AFV_BASIS[i][j];
+}
+
+/* AFV_IDCT of I.2.2: samples[i] = sum_j coefficients[j] * AFV_BASIS[j][i]. */
+static void afv_idct(const double* c, double* out) {
+  for (int i = 0; i < 16; ++i) {
+    double acc = 0.0;
+    for (int j = 0; j < 16; ++j) acc += c[j] * AFV_BASIS[j][i];
+    out[i] = acc;
+  }
+}
+
+/* AFV_DCT of I.2.2: coefficients[i] = sum_j samples[j] * AFV_BASIS[i][j]. */
+static void afv_dct(const double* smp, double* out) {
+  for (int i = 0; i < 16; ++i) {
+    double acc = 0.0;
+    for (int j = 0; j < 16; ++j) acc += smp[j] * AFV_BASIS[i][j];
+    out[i] = acc;
+  }
+}
+
+/* I.2.4.5: IDCT 8 x 4.  Two halves 4 wide and 8 tall; half x takes the
+ * coefficients of columns x, x + 2, x + 4, x + 6 and fills pixel columns
+ * 4 x .. 4 x + 3 (reading: the draft leaves this placement unstated); the two
+ * DC values are coefficients (0, 0) +- (1, 0). */
+static void inv_dct8x4(const double* K, double* S) {
+  const double dcs[2] = {K[0] + K[1], K[0] - K[1]};
+  for (int x = 0; x < 2; ++x) {
+    double blk[32], out[32];
+    for (int iy = 0; iy < 8; ++iy)
+      for (int ix = 0; ix < 4; ++ix) blk[iy * 4 + ix] = K[iy * 8 + x + 2 * ix];
+    blk[0] = dcs[x];
+    idct_2d(4, 8, blk, out);
+    for (int iy = 0; iy < 8; ++iy)
+      for (int ix = 0; ix < 4; ++ix) S[iy * 8 + 4 * x + ix] = out[iy * 4 + ix];
+  }
+}
+
+/* I.2.4.6: IDCT 4 x 8.  Two halves 8 wide and 4 tall; half y takes the
+ * coefficients of rows y, y + 2, y + 4, y + 6 and fills pixel rows
+ * 4 y .. 4 y + 3; the two DC values are coefficients (0, 0) +- (0, 1).
+ * Reading: the printed dcs[x] inside the loop over y is dcs[y]. */
+static void inv_dct4x8(const double* K, double* S) {
+  const double dcs[2] = {K[0] + K[8], K[0] - K[8]};
+  for (int y = 0; y < 2; ++y) {
+    double blk[32], out[32];
+    for (int iy = 0; iy < 4; ++iy)
+      for (int ix = 0; ix < 8; ++ix) blk[iy * 8 + ix] = K[(y + 2 * iy) * 8 + ix];
+    blk[0] = dcs[y];
+    idct_2d(8, 4, blk, out);
+    for (int iy = 0; iy < 4; ++iy)
+      for (int ix = 0; ix < 8; ++ix) S[(4 * y + iy) * 8 + ix] = out[iy * 8 + ix];
+  }
+}
+
+/* I.2.4.7: AFV.  The four quarter DCs come from 4 x coefficients (0, 0),
+ * (1, 0), (0, 1), (1, 1) by a 2 x 2 Hadamard step; quarter (x, y) takes the
+ * coefficients (x + 2 ix, y + 2 iy), its AFV_IDCT is mirrored horizontally
+ * when x = 1 and vertically when y = 1. */
+static void inv_afv(const double* K, double* S) {
+  const double c1 = K[0] * 4.0, c2 = K[1] * 4.0, c3 = K[8] * 4.0, c4 = K[9] * 4.0;
+  const double dcs[4] = {c1 + c2 + c3 + c4, c1 + c2 - c3 - c4, c1 - c2 + c3 - c4,
+                         c1 - c2 - c3 + c4};
+  for (int y = 0; y < 2; ++y)
+    for (int x = 0; x < 2; ++x) {
+      double c[16], out[16];
+      for (int iy = 0; iy < 4; ++iy)
+        for (int ix = 0; ix < 4; ++ix) c[iy * 4 + ix] = K[(y + 2 * iy) * 8 + x + 2 * ix];
+      c[0] = dcs[y * 2 + x];
+      afv_idct(c, out);
+      for (int iy = 0; iy < 4; ++iy)
+        for (int ix = 0; ix < 4; ++ix)
+          S[(4 * y + iy) * 8 + 4 * x + ix] = out[(y ? 3 - iy : iy) * 4 + (x ? 3 - ix : ix)];
+    }
+}
+
 int orc_inverse_transform(int s, const double* K, double* S) {
   int32_t bx, by;
   if (!supported(s) || !orc_varblock_size(s, &bx, &by)) return ORC_E_STRATEGY;
   if (s == ORC_DCT2) inv_dct2(K, S);
   else if (s == ORC_DCT4) inv_dct4(K, S);
   else if (s == ORC_IDENTITY) inv_identity(K, S);
+  else if (s == ORC_DCT8X4) inv_dct8x4(K, S);
+  else if (s == ORC_DCT4X8) inv_dct4x8(K, S);
+  else if (s == ORC_AFV) inv_afv(K, S);
   else idct_2d(bx, by, K, S);
   return ORC_OK;
 }
@@ -355,12 +494,64 @@ static void fwd_identity(const double* S, double* K) {
   aux_dct2x2(tmp, 2, K);
 }
 
+/* I.2.3.5: DCT 8 x 4. */
+static void fwd_dct8x4(const double* S, double* K) {
+  for (int x = 0; x < 2; ++x) {
+    double blk[32], c[32];
+    for (int iy = 0; iy < 8; ++iy)
+      for (int ix = 0; ix < 4; ++ix) blk[iy * 4 + ix] = S[iy * 8 + 4 * x + ix];
+    fdct_2d(4, 8, blk, c);
+    for (int iy = 0; iy < 8; ++iy)
+      for (int ix = 0; ix < 4; ++ix) K[iy * 8 + x + 2 * ix] = c[iy * 4 + ix];
+  }
+  const double c0 = K[0], c1 = K[1];
+  K[0] = (c0 + c1) * 0.5;
+  K[1] = (c0 - c1) * 0.5;
+}
+
+/* I.2.3.6: DCT 4 x 8. */
+static void fwd_dct4x8(const double* S, double* K) {
+  for (int y = 0; y < 2; ++y) {
+    double blk[32], c[32];
+    for (int iy = 0; iy < 4; ++iy)
+      for (int ix = 0; ix < 8; ++ix) blk[iy * 8 + ix] = S[(4 * y + iy) * 8 + ix];
+    fdct_2d(8, 4, blk, c);
+    for (int iy = 0; iy < 4; ++iy)
+      for (int ix = 0; ix < 8; ++ix) K[(y + 2 * iy) * 8 + ix] = c[iy * 8 + ix];
+  }
+  const double c0 = K[0], c1 = K[8];
+  K[0] = (c0 + c1) * 0.5;
+  K[8] = (c0 - c1) * 0.5;
+}
+
+/* I.2.3.7: AFV. */
+static void fwd_afv(const double* S, double* K) {
+  for (int y = 0; y < 2; ++y)
+    for (int x = 0; x < 2; ++x) {
+      double smp[16], c[16];
+      for (int iy = 0; iy < 4; ++iy)
+        for (int ix = 0; ix < 4; ++ix)
+          smp[(y ? 3 - iy : iy) * 4 + (x ? 3 - ix : ix)] = S[(4 * y + iy) * 8 + 4 * x + ix];
+      afv_dct(smp, c);
+      for (int iy = 0; iy < 4; ++iy)
+        for (int ix = 0; ix < 4; ++ix) K[(y + 2 * iy) * 8 + x + 2 * ix] = c[iy * 4 + ix];
+    }
+  const double c1 = K[0] * 0.25, c2 = K[1] * 0.25, c3 = K[8] * 0.25, c4 = K[9] * 0.25;
+  K[0] = (c1 + c2 + c3 + c4) * 0.25;
+  K[1] = (c1 + c2 - c3 - c4) * 0.25;
+  K[8] = (c1 - c2 + c3 - c4) * 0.25;
+  K[9] = (c1 - c2 - c3 + c4) * 0.25;
+}
+
 int orc_forward_transform(int s, const double* S, double* K) {
   int32_t bx, by;
   if (!supported(s) || !orc_varblock_size(s, &bx, &by)) return ORC_E_STRATEGY;
   if (s == ORC_DCT2) fwd_dct2(S, K);
   else if (s == ORC_DCT4) fwd_dct4(S, K);
   else if (s == ORC_IDENTITY) fwd_identity(S, K);
+  else if (s == ORC_DCT8X4) fwd_dct8x4(S, K);
+  else if (s == ORC_DCT4X8) fwd_dct4x8(S, K);
+  else if (s == ORC_AFV) fwd_afv(S, K);
   else fdct_2d(bx, by, S, K);
   return ORC_OK;
 }
@@ -459,6 +650,27 @@ static const double P_IDENTITY[3][3] = {
     {221.50801256717435, 7087.151589594002, 4466.9924939259863},
     {29.535505378287006, 1454.6663024982124, 1368.041230099175},
     {9.2887405354132238, 23.982311358829531, 11.201853748207084}};
+/* DCT4x8 mode (used by DCT4x8 and, transposed, by DCT8x4): four distance
+ * bands per channel, two eccentricity bands of 0, per-channel multiplier 1.
+ * Reading: the third channel's opening brace is lost in print. */
+static const double DB_DCT4X8[3][4] = {
+    {17.142628543359718, -0.16269623020744692, -0.31194253026666783, -0.2151140670773547},
+    {4.6225628588812384, -0.82630200888366945, -1.0675229603596517, -0.17845290869168118},
+    {0.81188546639482984, -0.6594385811273854, -0.050082094097871593, -2.6843722511996204}};
+static const double P_DCT4X8[3] = {1.0, 1.0, 1.0};
+/* AFV mode: eight afv_weights per channel and two dct4multipliers. */
+static const double AFV_W[3][8] = {
+    {6368.834817724610816928, 232.1096058872860158351, 415.663547479750900044,
+     220.0720486370546864556, 329.818962738766012564, -0.9919974139384578, 0, -0.60},
+    {1608.323575150649711025, 67.2724358236086, 89.06657498438612, 64.07248898359674,
+     125.6541247697168638611, -2.2833978673775697, -0.14, -0.2485},
+    {195.927828574730424638, 21.841306388764952, 18.5279466567289584105, 12.573868715940659,
+     15.89916083965558, -0.41, -0.1608, 0}};
+static const double AFV_P[3][2] = {{1.0, 1.0}, {1.0, 1.0}, {1.0, 1.0}};
+static const double AFV_FREQS[16] = {
+    0, 0, 0.8517778890324296, 5.37778436506804, 0, 0, 4.734747904497923, 5.449245381693219,
+    1.6598270267479331, 4, 7.275749096817861, 10.423227632456525, 2.662932286148962,
+    7.630657783650829, 8.962388608184032, 12.97166202570235};
 static const double P_DCT2[3][6] = {{3840.0, 2560.0, 1280.0, 640.0, 480.0, 300.0},
                                     {960.0, 640.0, 320.0, 180.0, 140.0, 120.0},
                                     {640.0, 320.0, 128.0, 64.0, 32.0, 16.0}};
@@ -528,6 +740,53 @@ int orc_dequant_matrix(int s, int c, double* out) {
         w[y * 8 + x] = v;
         num[y * 8 + x] = 1.0;
       }
+  } else if (s == ORC_DCT4X8 || s == ORC_DCT8X4) {
+    /* The 8-column by 4-row matrix of the band procedure, copied to (x, y)
+     * from (x, y / 2); (0, 1) divided by the multiplier; transposed for
+     * DCT8x4.  Numerators as for DCT4 on the 4-point dimension (the rows of
+     * DCT4x8, the columns of DCT8x4) and I(8, pos) on the other. */
+    double w84[32], w48[64];
+    dct_weights(8, 4, DB_DCT4X8[c], 4, NULL, 2, w84);
+    for (int y = 0; y < 8; ++y)
+      for (int x = 0; x < 8; ++x) w48[y * 8 + x] = w84[(y / 2) * 8 + x];
+    w48[1 * 8 + 0] /= P_DCT4X8[c];
+    for (int y = 0; y < 8; ++y)
+      for (int x = 0; x < 8; ++x) {
+        if (s == ORC_DCT4X8) {
+          w[y * 8 + x] = w48[y * 8 + x];
+          num[y * 8 + x] = orc_scale_I(8, x) * orc_scale_I(4, y / 2) / 64.0;
+        } else {
+          w[y * 8 + x] = w48[x * 8 + y];
+          num[y * 8 + x] = orc_scale_I(4, x / 2) * orc_scale_I(8, y) / 64.0;
+        }
+      }
+  } else if (s == ORC_AFV) {
+    /* Band values: bands[0] = afv_weights[4], bands[i] = bands[i - 1] *
+     * factor(afv_weights[i + 4]) (reading: the printed factor reads index
+     * i + 1 while its test reads i + 4; the band parameters are 5..7).  Each
+     * value fills a 2 x 2 cell group (x, y) -> (2x .. 2x+1, 2y .. 2y+1). */
+    double bands[4];
+    bands[0] = AFV_W[c][4];
+    for (int i = 1; i < 4; ++i) bands[i] = bands[i - 1] * band_factor(AFV_W[c][i + 4]);
+    const double lo = 0.8517778890324296, hi = 12.1198851366699204;
+    double w4[16];
+    w4[0] = AFV_W[c][0];
+    w4[1 * 4 + 0] = AFV_W[c][1]; /* set_weight(0, 1): x = 0, y = 1 */
+    w4[0 * 4 + 1] = AFV_W[c][2]; /* set_weight(1, 0) */
+    w4[1 * 4 + 1] = AFV_W[c][3];
+    for (int y = 0; y < 4; ++y)
+      for (int x = 0; x < 4; ++x) {
+        if (x < 2 && y < 2) continue;
+        w4[y * 4 + x] = interpolate(AFV_FREQS[y * 4 + x] - lo, hi, bands, 4);
+      }
+    for (int y = 0; y < 8; ++y)
+      for (int x = 0; x < 8; ++x) {
+        w[y * 8 + x] = w4[(y / 2) * 4 + x / 2];
+        num[y * 8 + x] = 1.0;
+      }
+    w[0 * 8 + 1] *= AFV_P[c][0];
+    w[1 * 8 + 0] *= AFV_P[c][0];
+    w[1 * 8 + 1] *= AFV_P[c][1];
   } else if (s == ORC_DCT4) {
     double w4[16];
     dct_weights(4, 4, DB_DCT4[c], 4, NULL, 2, w4);

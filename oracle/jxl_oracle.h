@@ -90,6 +90,8 @@ double orc_scale_I(int32_t N, int32_t u);
 double orc_scale_D(int32_t N, int32_t u);
 double orc_scalef(int32_t N, int32_t n, int32_t x);
 /* Inverse transform of one varblock (I.2.4): coefficients [by][bx] -> samples [by][bx]. */
+/* The AFV basis of I.2.2 as a 16 x 16 row-major array (row i = basis vector i). */
+void orc_afv_basis(double* out);
 int orc_inverse_transform(int strategy, const double* coeffs, double* samples);
 /* Forward transform of one varblock (I.2.3); used by round-trip pins only. */
 int orc_forward_transform(int strategy, const double* samples, double* coeffs);

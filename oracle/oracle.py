@@ -65,6 +65,7 @@ def lib():
         L.orc_llf_from_dc.argtypes = [C.c_int, _f64p, _f64p]
         L.orc_dc_from_llf.argtypes = [C.c_int, _f64p, _f64p]
         L.orc_dequant_matrix.argtypes = [C.c_int, C.c_int, _f64p]
+        L.orc_afv_basis.argtypes = [_f64p]
         ptr3 = C.c_void_p * 3
         L.orc_reconstruct.argtypes = [P, ptr3, ptr3, _u8p, _u8p, _f32p, _f32p, _f64p]
         L.orc_epf_mul_table.argtypes = [C.c_int32, _i32p]
@@ -93,7 +94,7 @@ def _check(st):
 STRATEGY_NAMES = ["DCT8", "IDENTITY", "DCT2", "DCT4", "DCT16", "DCT32", "DCT16X8",
                   "DCT8X16", "DCT32X8", "DCT8X32", "DCT32X16", "DCT16X32",
                   "DCT4X8", "DCT8X4", "AFV"]
-SUPPORTED = list(range(12))
+SUPPORTED = list(range(15))
 
 
 def varblock_size(s):
@@ -180,6 +181,12 @@ def dc_from_llf(s, llf):
     out = np.zeros((cy, cx))
     _check(lib().orc_dc_from_llf(s, L, out))
     return out
+
+
+def afv_basis():
+    out = np.zeros(256)
+    lib().orc_afv_basis(out)
+    return out.reshape(16, 16)
 
 
 def dequant_matrix(s, c):

@@ -16,7 +16,10 @@ import scipy.ndimage as ndi
 from oracle import oracle as O
 
 DCT_FAMILY = [0, 4, 5, 6, 7, 8, 9, 10, 11]
-EIGHT_CLASS = [1, 2, 3]
+EIGHT_CLASS = [1, 2, 3, 12, 13, 14]
+# forward (I.2.3) then inverse (I.2.4) of the 8 x 8 classes: a multiple of
+# the identity with this gain
+EIGHT_GAIN = {1: 1.0, 2: 1.0, 3: 16.0, 12: 32.0, 13: 32.0, 14: 1.0}
 
 
 # --------------------------------------------------------------------------
@@ -255,7 +258,8 @@ def test_dct_family_is_direct_cosine_sum(s):
 
 
 @pytest.mark.parametrize("s,gain", [(0, 64), (4, 256), (5, 1024), (6, 128), (7, 128), (8, 256),
-                                    (9, 256), (10, 512), (11, 512), (1, 1), (2, 1), (3, 16)])
+                                    (9, 256), (10, 512), (11, 512), (1, 1), (2, 1), (3, 16),
+                                    (12, 32), (13, 32), (14, 1)])
 def test_round_trip_forward_then_inverse(s, gain):
     # I.2.3 (forward) followed by I.2.4 (inverse): a multiple of the identity.
     bx, by = O.varblock_size(s)
@@ -267,7 +271,7 @@ def test_round_trip_forward_then_inverse(s, gain):
 @pytest.mark.parametrize("s", EIGHT_CLASS)
 def test_eight_class_inverse_is_inverse_of_forward_map(s):
     # The inverse map equals numpy's inverse of the forward map (times the gain).
-    gain = {1: 1.0, 2: 1.0, 3: 16.0}[s]
+    gain = EIGHT_GAIN[s]
     F = np.stack([O.forward_transform(s, e.reshape(8, 8)).ravel() for e in np.eye(64)], axis=1)
     G = np.stack([O.inverse_transform(s, e.reshape(8, 8)).ravel() for e in np.eye(64)], axis=1)
     np.testing.assert_allclose(G, gain * np.linalg.inv(F), atol=1e-10)
@@ -280,7 +284,67 @@ def test_forward_of_constant_block_is_dc_only():
         dc = K[0, 0]
         K[0, 0] = 0.0
         assert np.abs(K).max() < 1e-13 * abs(dc), s
-        assert dc == pytest.approx(3.25 * ({1: 1, 2: 1, 3: 16}.get(s, bx * by)), rel=1e-12)
+        assert dc == pytest.approx(3.25 * EIGHT_GAIN.get(s, bx * by), rel=1e-12)
+
+
+@pytest.mark.parametrize("s", [12, 13])
+def test_half_block_transforms_are_direct_cosine_sums(s):
+    # I.2.4.5 / I.2.4.6 brute force: each half is a 4 x 8 (or 8 x 4) inverse
+    # built from the draft's 1-D maps, fed with every second column (row) of
+    # coefficients and the DC pair combined as (0, 0) +- (1, 0) (or (0, 1));
+    # DCT8x4's halves are the left and right pixel columns, DCT4x8's the top
+    # and bottom pixel rows.
+    K = _rng(40 + s).standard_normal((8, 8))
+    S = O.inverse_transform(s, K)
+    T4, T8 = draft_inverse_matrix(4), draft_inverse_matrix(8)
+    ref = np.zeros((8, 8))
+    for h in range(2):
+        if s == 13:
+            blk = K[:, h::2].copy()  # 8 rows x 4 columns
+            blk[0, 0] = K[0, 0] + K[0, 1] if h == 0 else K[0, 0] - K[0, 1]
+            out = np.zeros((8, 4))
+            for n in range(8):
+                for m in range(4):
+                    out[n, m] = sum(T8[n, k] * T4[m, l] * blk[k, l] for k in range(8) for l in range(4))
+            ref[:, 4 * h:4 * h + 4] = out
+        else:
+            blk = K[h::2, :].copy()  # 4 rows x 8 columns
+            blk[0, 0] = K[0, 0] + K[1, 0] if h == 0 else K[0, 0] - K[1, 0]
+            out = np.zeros((4, 8))
+            for n in range(4):
+                for m in range(8):
+                    out[n, m] = sum(T4[n, k] * T8[m, l] * blk[k, l] for k in range(4) for l in range(8))
+            ref[4 * h:4 * h + 4, :] = out
+    np.testing.assert_allclose(S, ref, atol=1e-11)
+
+
+def test_afv_basis_is_orthonormal():
+    # The AFV basis as the oracle holds it (after the two 17-entry rows are
+    # repaired): orthonormal, its first row the constant 1/4.
+    B = O.afv_basis()
+    np.testing.assert_allclose(B @ B.T, np.eye(16), atol=2e-14)
+    np.testing.assert_allclose(B[0], np.full(16, 0.25), atol=0)
+
+
+@pytest.mark.parametrize("qx,qy", [(0, 0), (1, 0), (0, 1), (1, 1)])
+def test_afv_quarter_is_mirrored_basis_row(qx, qy):
+    # One coefficient of one quarter (outside the 2 x 2 DC corner): the output
+    # is that basis row in the quarter, mirrored horizontally for qx = 1 and
+    # vertically for qy = 1, and zero elsewhere.
+    B = O.afv_basis()
+    for j in (3, 6, 15):
+        ix, iy = j % 4, j // 4
+        K = np.zeros((8, 8))
+        K[qy + 2 * iy, qx + 2 * ix] = 1.0
+        S = O.inverse_transform(14, K)
+        q = B[j].reshape(4, 4)  # [y][x]
+        if qx:
+            q = q[:, ::-1]
+        if qy:
+            q = q[::-1, :]
+        ref = np.zeros((8, 8))
+        ref[4 * qy:4 * qy + 4, 4 * qx:4 * qx + 4] = q
+        np.testing.assert_allclose(S, ref, atol=1e-15)
 
 
 def test_identity_forward_keeps_sample_differences():
@@ -379,16 +443,53 @@ def test_cropping_keeps_top_left_samples():
 # --------------------------------------------------------------------------
 
 def test_dequant_matrices_positive_and_symmetric():
-    for s in range(12):
+    for s in range(15):
         bx, by = O.varblock_size(s)
         for c in range(3):
             m = O.dequant_matrix(s, c)
             assert np.all(np.isfinite(m.ravel()[1:])) and np.all(m.ravel()[1:] > 0)
-            if bx == by:
+            if bx == by and s not in (12, 13, 14):
                 np.testing.assert_allclose(m, m.T, rtol=1e-13)
-    for a, b in [(6, 7), (8, 9), (10, 11)]:
+    for a, b in [(6, 7), (8, 9), (10, 11), (12, 13)]:
         for c in range(3):
             np.testing.assert_allclose(O.dequant_matrix(a, c), O.dequant_matrix(b, c).T, rtol=1e-13)
+
+
+# AFV defaults of C.6.1.1 (afv_weights per channel; the multipliers are 1)
+AFV_DEFAULT = [[6368.834817724610816928, 232.1096058872860158351, 415.663547479750900044,
+                220.0720486370546864556, 329.818962738766012564, -0.9919974139384578, 0, -0.60],
+               [1608.323575150649711025, 67.2724358236086, 89.06657498438612, 64.07248898359674,
+                125.6541247697168638611, -2.2833978673775697, -0.14, -0.2485],
+               [195.927828574730424638, 21.841306388764952, 18.5279466567289584105,
+                12.573868715940659, 15.89916083965558, -0.41, -0.1608, 0]]
+
+
+@pytest.mark.parametrize("c", [0, 1, 2])
+def test_dequant_afv_defaults(c):
+    # The four low 2 x 2 cell groups hold 1 / afv_weights[0..3] (the numerators
+    # are 1): group (0, 0) = the quarter DCs, (0, 1) at rows 2-3, (1, 0) at
+    # columns 2-3, (1, 1); the highest frequency (kFreqs 12.97, 1e-6 below
+    # the top of the printed range) takes the last band, afv_weights[4] times
+    # the three band factors, to within the 1e-7 that gap makes.
+    m = O.dequant_matrix(14, c)  # [y][x]
+    a = AFV_DEFAULT[c]
+    np.testing.assert_allclose(m[0:2, 0:2].ravel()[1:], 1.0 / a[0], rtol=1e-14)
+    np.testing.assert_allclose(m[2:4, 0:2], 1.0 / a[1], rtol=1e-14)
+    np.testing.assert_allclose(m[0:2, 2:4], 1.0 / a[2], rtol=1e-14)
+    np.testing.assert_allclose(m[2:4, 2:4], 1.0 / a[3], rtol=1e-14)
+    f = lambda v: v + 1 if v > 0 else 1 / (1 - v)
+    last = a[4] * f(a[5]) * f(a[6]) * f(a[7])
+    np.testing.assert_allclose(m[6:8, 6:8], 1.0 / last, rtol=3e-7)
+
+
+def test_dequant_dct4x8_dc_pair_shares_the_dc_weight():
+    # C.6.1 DCT4x8 mode: (x, y) takes the 8 x 4 band matrix at (x, y / 2), so
+    # the second half's DC slot (0, 1) has the DC weight (multiplier 1) and
+    # the DC numerator; DCT8x4 is the transpose.
+    for c in range(3):
+        m = O.dequant_matrix(12, c)
+        assert m[1, 0] == pytest.approx(m[0, 0], rel=1e-15)
+        np.testing.assert_allclose(O.dequant_matrix(13, c), m.T, rtol=1e-15)
 
 
 def test_dequant_dct16_at_band_point():
@@ -463,7 +564,7 @@ def test_ill_formed_maps_are_rejected():
     with pytest.raises(O.OracleError):
         O.reconstruct(p, f)
     f = _frame_of(0, W, H, dc)
-    f["strategy"][0, 0] = 14  # AFV: not reconstructed by this oracle
+    f["strategy"][0, 0] = 15  # not a C.5.4 value
     with pytest.raises(O.OracleError):
         O.reconstruct(p, f)
 
