@@ -902,9 +902,9 @@ int orc_reconstruct(const orc_params* p, const int32_t* const ac[3], const int32
   const int32_t Wt = (W + 63) / 64;   /* CfL tiles per row */
 
   /* Dequantization matrices per transform type and channel. */
-  double (*dq)[3][1024] = (double (*)[3][1024])malloc(sizeof(double) * 12 * 3 * 1024);
+  double (*dq)[3][1024] = (double (*)[3][1024])malloc(sizeof(double) * 15 * 3 * 1024);
   if (!dq) return ORC_E_SIZE;
-  for (int s = 0; s < 12; ++s)
+  for (int s = 0; s < 15; ++s)
     for (int c = 0; c < 3; ++c) {
       st = orc_dequant_matrix(s, c, dq[s][c]);
       if (st) { free(dq); return st; }
