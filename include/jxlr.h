@@ -54,9 +54,10 @@ typedef enum {
 } jxlr_status;
 
 /* Transform types; numbering of the C.5.4 table.  This library reconstructs
- * types 0..11 (DCT4X8, DCT8X4 and AFV are rejected with JXLR_E_STRATEGY).
- * "DCT N x M" covers bxsize = max(8, N) by bysize = max(8, M) pixels (I.2.5):
- * the first number is the width. */
+ * all fifteen (inverse transforms of I.2.4.1-I.2.4.7); values from 15 up are
+ * rejected with JXLR_E_STRATEGY.  "DCT N x M" covers bxsize = max(8, N) by
+ * bysize = max(8, M) pixels (I.2.5): the first number is the width; DCT4X8,
+ * DCT8X4 and AFV cover 8 x 8. */
 typedef enum {
   JXLR_DCT8 = 0, JXLR_IDENTITY = 1, JXLR_DCT2 = 2, JXLR_DCT4 = 3, JXLR_DCT16 = 4,
   JXLR_DCT32 = 5, JXLR_DCT16X8 = 6, JXLR_DCT8X16 = 7, JXLR_DCT32X8 = 8,

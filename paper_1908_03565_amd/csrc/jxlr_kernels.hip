@@ -48,18 +48,19 @@ constexpr int kInfoThreads = 64;
 constexpr uint8_t kAbsent = 0xFF;
 
 // Varblock size in blocks of transform type s (I.2.5): "DCT N x M" is N wide.
-// One nibble per type, types 0..11; branch-free on the device.
+// One nibble per type, types 0..14; branch-free on the device.
 __host__ __device__ constexpr int vb_bx(int s) {
-  return int((0x241412421111ull >> (4 * (s & 15))) & 0xFu);
+  return int((0x111241412421111ull >> (4 * (s & 15))) & 0xFu);
 }
 __host__ __device__ constexpr int vb_by(int s) {
-  return int((0x424121421111ull >> (4 * (s & 15))) & 0xFu);
+  return int((0x111424121421111ull >> (4 * (s & 15))) & 0xFu);
 }
 static_assert(vb_bx(4) == 2 && vb_by(4) == 2 && vb_bx(5) == 4 && vb_by(5) == 4 &&
                   vb_bx(6) == 2 && vb_by(6) == 1 && vb_bx(7) == 1 && vb_by(7) == 2 &&
                   vb_bx(8) == 4 && vb_by(8) == 1 && vb_bx(9) == 1 && vb_by(9) == 4 &&
                   vb_bx(10) == 4 && vb_by(10) == 2 && vb_bx(11) == 2 && vb_by(11) == 4 &&
-                  vb_bx(3) == 1 && vb_by(0) == 1,
+                  vb_bx(3) == 1 && vb_by(0) == 1 && vb_bx(12) == 1 && vb_by(12) == 1 &&
+                  vb_bx(13) == 1 && vb_by(13) == 1 && vb_bx(14) == 1 && vb_by(14) == 1,
               "varblock sizes of the C.5.4 table");
 // Offset of type s inside DeviceTables::dq.
 __host__ __device__ constexpr int dq_off(int s) {
@@ -68,7 +69,8 @@ __host__ __device__ constexpr int dq_off(int s) {
   return off;
 }
 static_assert(dq_off(jxlr::kNumStrategies) == jxlr::kDqFloats, "dequant table layout");
-static_assert(dq_off(5) == 8 * 192 && dq_off(6) == 24 * 192 && dq_off(11) == 44 * 192,
+static_assert(dq_off(5) == 8 * 192 && dq_off(6) == 24 * 192 && dq_off(11) == 44 * 192 &&
+                  dq_off(12) == 52 * 192 && dq_off(14) == 54 * 192,
               "packed offsets of dq_off_lut");
 
 __device__ inline int mirror(int c, int size) {
@@ -226,6 +228,50 @@ __device__ inline void identity_inverse(float (&v)[64]) {
     }
 }
 
+// I.2.4.7 AFV on an 8x8 block in LDS (row stride ld), in place: the four
+// quarter DCs from 4 x the 2x2 corner by a Hadamard step, then per quarter
+// the 16-term AFV_IDCT (basis B[j][i] from the tables) of its interleaved
+// coefficients, mirrored horizontally for the right and vertically for the
+// bottom quarters.  The four quarters advance together over the basis
+// vectors (one vector's 16 values live at a time); every coefficient is read
+// before any sample is written.
+__device__ inline void afv_inverse(float* base, int ld, const float (*__restrict__ B)[16]) {
+  float acc[4][16];
+  {
+    const float c1 = 4.0f * base[0], c2 = 4.0f * base[1];
+    const float c3 = 4.0f * base[ld], c4 = 4.0f * base[ld + 1];
+    const float dcs[4] = {c1 + c2 + c3 + c4, c1 + c2 - c3 - c4, c1 - c2 + c3 - c4,
+                          c1 - c2 - c3 + c4};
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int i = 0; i < 16; ++i) acc[q][i] = dcs[q] * B[0][i];
+  }
+#pragma unroll 1
+  for (int j = 1; j < 16; ++j) {
+    const int ix = j & 3, iy = j >> 2;
+    float kq[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) kq[q] = base[((q >> 1) + 2 * iy) * ld + (q & 1) + 2 * ix];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const float bv = B[j][i];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc[q][i] = fmaf(kq[q], bv, acc[q][i]);
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int qx = q & 1, qy = q >> 1;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      // sample index i = 4 y + x of the quarter lands mirrored
+      const int y = qy ? 3 - (i >> 2) : (i >> 2), x = qx ? 3 - (i & 3) : (i & 3);
+      base[(4 * qy + y) * ld + 4 * qx + x] = acc[q][i];
+    }
+  }
+}
+
 struct ReconArgs {
   int W, H, Wb, Hb;
   const int32_t* ac[3];
@@ -322,9 +368,10 @@ __device__ inline void segment_dct4(float* v, int st) {
 }
 
 // The column or row segment that starts at `v`: one varblock dimension of n
-// samples of type s.
-__device__ inline void segment(float* v, int st, int s, int n) {
-  if (s == 3) segment_dct4(v, st);
+// samples; `four`: the dimension is two interleaved 4-point transforms (DCT4
+// both ways, DCT4x8 along columns, DCT8x4 along rows).
+__device__ inline void segment(float* v, int st, bool four, int n) {
+  if (four) segment_dct4(v, st);
   else if (n == 8) segment_dct<8>(v, st);
   else if (n == 16) segment_dct<16>(v, st);
   else segment_dct<32>(v, st);
@@ -335,11 +382,12 @@ constexpr int kRecTW = 64, kRecTH = 32;  // two 32x32 regions side by side
 constexpr int kRecLd = kRecTW + 1;
 
 // Offset of type s inside DeviceTables::dq / dqs, as dq_off, from a byte
-// table packed in two integers (units of 192 floats: three channels of 64).
+// table packed in two integers (units of 192 floats: three channels of 64);
+// types 12..14 (one block each) follow at 52, 53, 54.
 __device__ inline int dq_off_lut(int s) {
   constexpr uint64_t lo = 0x1A18080403020100ull;  // types 0..7: 0 1 2 3 4 8 24 26
   constexpr uint32_t hi = 0x2C24201Cu;            // types 8..11: 28 32 36 44
-  const uint32_t v = s < 8 ? uint32_t(lo >> (8 * s)) : (hi >> (8 * (s - 8)));
+  const uint32_t v = s < 8 ? uint32_t(lo >> (8 * s)) : s < 12 ? (hi >> (8 * (s - 8))) : uint32_t(40 + s);
   return int(v & 0xFFu) * 192;
 }
 
@@ -518,7 +566,7 @@ __device__ __attribute__((always_inline)) inline void recon_tile(const ReconArgs
     if (a.split) {
       // one DCT type over the whole region (then its varblocks tile it)
       const int s0 = s_strat[tid][0];
-      bool uni = s0 != kAbsent && s0 != 1 && s0 != 2 && s0 != 3;
+      bool uni = s0 != kAbsent && s0 != 1 && s0 != 2 && s0 != 3 && s0 < 12;
       for (int i = 1; i < 16; ++i) uni = uni && s_strat[tid][i] == s0;
       if (uni) m = (vb_by(s0) >> 1) | ((vb_bx(s0) >> 1) << 2);
     }
@@ -598,12 +646,22 @@ __device__ __attribute__((always_inline)) inline void recon_tile(const ReconArgs
   }
   __syncthreads();
 
-  // 8x8 transforms that are not separable products: DCT2 and Identity, and
-  // the 2x2 corner step of DCT4 (I.2.4.2-I.2.4.4).  Wave c: channel c.
+  // 8x8 transforms that are not separable products: DCT2, Identity and AFV,
+  // the 2x2 corner step of DCT4 and the DC pair of the two halves of DCT4x8
+  // and DCT8x4 (I.2.4.2-I.2.4.7).  Wave c: channel c.
   if (lane < 32) {
     const int c = wave, r = lane >> 4, lb = lane & 15;
     const int s = s_strat[r][lb];
-    if (s == 1 || s == 2 || s == 3) {
+    float* base = &coef[c][8 * (lb >> 2)][32 * r + 8 * (lb & 3)];
+    if (s == 12 || s == 13) {
+      // (0, 0) +- (0, 1) for DCT4x8 (halves stacked), (0, 0) +- (1, 0) for DCT8x4
+      const int o = s == 12 ? kRecLd : 1;
+      const float a0 = base[0], a1 = base[o];
+      base[0] = a0 + a1;
+      base[o] = a0 - a1;
+    } else if (s == 14) {
+      afv_inverse(base, kRecLd, T->afv);
+    } else if (s == 1 || s == 2 || s == 3) {
       float* base = &coef[c][8 * (lb >> 2)][32 * r + 8 * (lb & 3)];
       float v[64];
 #pragma unroll
@@ -637,9 +695,10 @@ __device__ __attribute__((always_inline)) inline void recon_tile(const ReconArgs
     for (int br = 0; br < 4; ++br) {
       const int lb = br * 4 + ((X & 31) >> 3);
       const int s = s_strat[r][lb];
-      if (s == kAbsent || s == 1 || s == 2 || (s_owner[r][lb] >> 2) != br || s_mma[r] >= 0)
+      if (s == kAbsent || s == 1 || s == 2 || s == 14 || (s_owner[r][lb] >> 2) != br ||
+          s_mma[r] >= 0)
         continue;
-      segment(&coef[c][8 * br][X], kRecLd, s, 8 * vb_by(s));
+      segment(&coef[c][8 * br][X], kRecLd, s == 3 || s == 12, 8 * vb_by(s));
     }
   }
   __syncthreads();
@@ -650,9 +709,10 @@ __device__ __attribute__((always_inline)) inline void recon_tile(const ReconArgs
     for (int bc = 0; bc < 4; ++bc) {
       const int lb = (Y >> 3) * 4 + bc;
       const int s = s_strat[r][lb];
-      if (s == kAbsent || s == 1 || s == 2 || (s_owner[r][lb] & 3) != bc || s_mma[r] >= 0)
+      if (s == kAbsent || s == 1 || s == 2 || s == 14 || (s_owner[r][lb] & 3) != bc ||
+          s_mma[r] >= 0)
         continue;
-      segment(&coef[c][Y][32 * r + 8 * bc], 1, s, 8 * vb_bx(s));
+      segment(&coef[c][Y][32 * r + 8 * bc], 1, s == 3 || s == 13, 8 * vb_bx(s));
     }
   }
   __syncthreads();

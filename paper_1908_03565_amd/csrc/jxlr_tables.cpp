@@ -103,6 +103,89 @@ const BandSet kDist32x16 = {8,
                               -0.79014862079498627, -0.2692727459704829, -0.38272769465388551,
                               -0.2292422253091453, -0.20719098826199578},
                              {0.098, -2.41, -0.23, -0.2, -0.4, -0.8, -0.4, -0.5}}};
+// DCT4x8 mode (DCT4x8, and transposed DCT8x4): four distance bands, two
+// eccentricity bands of zero, one multiplier per channel.
+const BandSet kDist4x8 = {4,
+                          {{17.142628543359718, -0.16269623020744692, -0.31194253026666783,
+                            -0.2151140670773547},
+                           {4.6225628588812384, -0.82630200888366945, -1.0675229603596517,
+                            -0.17845290869168118},
+                           {0.81188546639482984, -0.6594385811273854, -0.050082094097871593,
+                            -2.6843722511996204}}};
+const double kDct4x8Mul[3] = {1.0, 1.0, 1.0};
+// AFV mode: afv_weights (four 2x2-group weights, the first band value and
+// three band parameters) and the two multipliers, per channel; the
+// frequency of each 4x4 position and the range they are mapped from.
+const double kAfvW[3][8] = {
+    {6368.834817724610816928, 232.1096058872860158351, 415.663547479750900044,
+     220.0720486370546864556, 329.818962738766012564, -0.9919974139384578, 0, -0.60},
+    {1608.323575150649711025, 67.2724358236086, 89.06657498438612, 64.07248898359674,
+     125.6541247697168638611, -2.2833978673775697, -0.14, -0.2485},
+    {195.927828574730424638, 21.841306388764952, 18.5279466567289584105, 12.573868715940659,
+     15.89916083965558, -0.41, -0.1608, 0}};
+const double kAfvMul[3][2] = {{1.0, 1.0}, {1.0, 1.0}, {1.0, 1.0}};
+const double kAfvFreq[16] = {0, 0, 0.8517778890324296, 5.37778436506804, 0, 0,
+                             4.734747904497923, 5.449245381693219, 1.6598270267479331, 4,
+                             7.275749096817861, 10.423227632456525, 2.662932286148962,
+                             7.630657783650829, 8.962388608184032, 12.97166202570235};
+const double kAfvLo = 0.8517778890324296, kAfvHi = 12.1198851366699204;
+// The AFV basis (I.2.2), vector i = row i, 4x4 entry (x, y) at 4 y + x; the
+// two rows printed with 17 entries are taken with their spurious zero
+// removed (row 4 the last, row 9 the one at index 3), which makes the basis
+// orthonormal.
+const double kAfvBasis[16][16] = {
+    {0.25, 0.25, 0.25, 0.25, 0.25, 0.25, 0.25, 0.25, 0.25, 0.25, 0.25, 0.25, 0.25, 0.25, 0.25,
+     0.25},
+    {0.876902929799142, 0.2206518106944235, -0.10140050393753763, -0.1014005039375375,
+     0.2206518106944236, -0.10140050393753777, -0.10140050393753772, -0.10140050393753763,
+     -0.10140050393753758, -0.10140050393753769, -0.1014005039375375, -0.10140050393753768,
+     -0.10140050393753768, -0.10140050393753759, -0.10140050393753763, -0.10140050393753741},
+    {0.0, 0.0, 0.40670075830260755, 0.44444816619734445, 0.0, 0.0, 0.19574399372042936,
+     0.2929100136981264, -0.40670075830260716, -0.19574399372042872, 0.0, 0.11379074460448091,
+     -0.44444816619734384, -0.29291001369812636, -0.1137907446044814, 0.0},
+    {0.0, 0.0, -0.2125574805828748, 0.3085497062849767, 0.0, 0.4706702258572536,
+     -0.1621205195722993, 0.0, -0.21255748058287047, -0.16212051957228327, -0.47067022585725277,
+     -0.1464291867126764, 0.3085497062849487, 0.0, -0.1464291867126536, 0.4251149611657548},
+    {0.0, -0.7071067811865474, 0.0, 0.0, 0.7071067811865476, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0,
+     0.0, 0.0, 0.0, 0.0},
+    {-0.4105377591765233, 0.6235485373547691, -0.06435071657946274, -0.06435071657946266,
+     0.6235485373547694, -0.06435071657946284, -0.0643507165794628, -0.06435071657946274,
+     -0.06435071657946272, -0.06435071657946279, -0.06435071657946266, -0.06435071657946277,
+     -0.06435071657946277, -0.06435071657946273, -0.06435071657946274, -0.0643507165794626},
+    {0.0, 0.0, -0.4517556589999482, 0.15854503551840063, 0.0, -0.04038515160822202,
+     0.0074182263792423875, 0.39351034269210167, -0.45175565899994635, 0.007418226379244351,
+     0.1107416575309343, 0.08298163094882051, 0.15854503551839705, 0.3935103426921022,
+     0.0829816309488214, -0.45175565899994796},
+    {0.0, 0.0, -0.304684750724869, 0.5112616136591823, 0.0, 0.0, -0.290480129728998,
+     -0.06578701549142804, 0.304684750724884, 0.2904801297290076, 0.0, -0.23889773523344604,
+     -0.5112616136592012, 0.06578701549142545, 0.23889773523345467, 0.0},
+    {0.0, 0.0, 0.3017929516615495, 0.25792362796341184, 0.0, 0.16272340142866204,
+     0.09520022653475037, 0.0, 0.3017929516615503, 0.09520022653475055, -0.16272340142866173,
+     -0.35312385449816297, 0.25792362796341295, 0.0, -0.3531238544981624, -0.6035859033230976},
+    {0.0, 0.0, 0.40824829046386274, 0.0, 0.0, 0.0, 0.0, -0.4082482904638628, -0.4082482904638635,
+     0.0, 0.0, -0.40824829046386296, 0.0, 0.408248290463863, 0.408248290463863, 0.0},
+    {0.0, 0.0, 0.1747866975480809, 0.0812611176717539, 0.0, 0.0, -0.3675398009862027,
+     -0.307882213957909, -0.17478669754808135, 0.3675398009862011, 0.0, 0.4826689115059883,
+     -0.08126111767175039, 0.30788221395790305, -0.48266891150598584, 0.0},
+    {0.0, 0.0, -0.21105601049335784, 0.18567180916109802, 0.0, 0.0, 0.49215859013738733,
+     -0.38525013709251915, 0.21105601049335806, -0.49215859013738905, 0.0, 0.17419412659916217,
+     -0.18567180916109904, 0.3852501370925211, -0.1741941265991621, 0.0},
+    {0.0, 0.0, -0.14266084808807264, -0.3416446842253372, 0.0, 0.7367497537172237,
+     0.24627107722075148, -0.08574019035519306, -0.14266084808807344, 0.24627107722075137,
+     0.14883399227113567, -0.04768680350229251, -0.3416446842253373, -0.08574019035519267,
+     -0.047686803502292804, -0.14266084808807242},
+    {0.0, 0.0, -0.13813540350758585, 0.3302282550303788, 0.0, 0.08755115000587084,
+     -0.07946706605909573, -0.4613374887461511, -0.13813540350758294, -0.0794670660591026,
+     0.49724647109535086, 0.12538059448563663, 0.3302282550303805, -0.4613374887461554,
+     0.12538059448564315, -0.13813540350758452},
+    {0.0, 0.0, -0.1743760259965106, 0.0702790691196284, 0.0, -0.2921026642334881,
+     0.3623817333531167, 0.0, -0.1743760259965108, 0.36238173335311646, 0.29210266423348785,
+     -0.4326608024727445, 0.07027906911962818, 0.0, -0.4326608024727457, 0.34875205199302267},
+    {0.0, 0.0, 0.1135498731499337, -0.07417504595810355, 0.0, 0.19402893032594343,
+     -0.435190496523228, 0.21918684838857466, 0.11354987314994257, -0.4351904965232251,
+     0.5550443808910661, -0.25468277124066463, -0.07417504595810233, 0.2191868483885728,
+     -0.25468277124066413, 0.1135498731499429},
+};
 const double kIdentityW[3][3] = {{221.50801256717435, 7087.151589594002, 4466.9924939259863},
                                  {29.535505378287006, 1454.6663024982124, 1368.041230099175},
                                  {9.2887405354132238, 23.982311358829531, 11.201853748207084}};
@@ -182,6 +265,35 @@ bool dequant_matrix_f64(int s, int c, double* out) {
           if (k >= 0) at(w, x, y) = kDct2W[c][k];
         }
       break;
+    }
+    case 12:
+    case 13: {  // DCT4x8 mode: 8x4 band matrix at (x, y / 2); DCT8x4 transposed
+      std::vector<double> w84 = band_weights(8, 4, kDist4x8, nullptr, c, 2);
+      for (int y = 0; y < 8; ++y)
+        for (int x = 0; x < 8; ++x) {
+          const int u = s == 12 ? x : y, v = s == 12 ? y : x;  // 8-point, 4-point axis
+          double wv = w84[(v / 2) * 8 + u];
+          if (u == 0 && v == 1) wv /= kDct4x8Mul[c];
+          at(w, x, y) = wv;
+          at(num, x, y) = scale_i(8, u) * scale_i(4, v / 2) / 64.0;
+        }
+      break;
+    }
+    case 14: {  // AFV mode: 4x4 values, each covering a 2x2 cell group
+      std::vector<double> bands = cumulative(kAfvW[c][4], &kAfvW[c][5], 3);
+      double w4[16];
+      w4[0] = kAfvW[c][0];
+      w4[4] = kAfvW[c][1];  // group (0, 1)
+      w4[1] = kAfvW[c][2];  // group (1, 0)
+      w4[5] = kAfvW[c][3];
+      for (int i = 0; i < 16; ++i)
+        if ((i & 3) >= 2 || i >= 8) w4[i] = interp(kAfvFreq[i] - kAfvLo, kAfvHi, bands);
+      for (int y = 0; y < 8; ++y)
+        for (int x = 0; x < 8; ++x) at(w, x, y) = w4[(y / 2) * 4 + x / 2];
+      at(w, 1, 0) *= kAfvMul[c][0];
+      at(w, 0, 1) *= kAfvMul[c][0];
+      at(w, 1, 1) *= kAfvMul[c][1];
+      break;  // numerators 1
     }
     case 3: {  // DCT4 mode: 4x4 band matrix, each entry covering 2x2
       std::vector<double> w4 = band_weights(4, 4, kDist4, nullptr, c, 2);
@@ -358,6 +470,8 @@ bool build_tables(DeviceTables* t) {
       }
   }
   build_mfma_operands(t);
+  for (int j = 0; j < 16; ++j)
+    for (int i = 0; i < 16; ++i) t->afv[j][i] = float(kAfvBasis[j][i]);
   srgb_thresholds(8, t->srgb_thr8);
   srgb_thresholds(16, t->srgb_thr16);
   if (!srgb_bucket_starts(t->srgb_start8)) return false;
@@ -370,6 +484,9 @@ bool build_tables(DeviceTables* t) {
         const int x = i % X, y = i / X;
         double sc = 1.0;
         if (s == 3) sc = transform_scale(4, y / 2) * transform_scale(4, x / 2);
+        else if (s == 12) sc = transform_scale(4, y / 2) * transform_scale(8, x);
+        else if (s == 13) sc = transform_scale(8, y) * transform_scale(4, x / 2);
+        else if (s == 14) sc = 1.0;
         else if (s != 1 && s != 2) sc = transform_scale(Y, y) * transform_scale(X, x);
         t->dq[dq_offset(s) + c * sz + i] = float(dq[i]);
         t->dqs[dq_offset(s) + c * sz + i] = float(dq[i] * sc);

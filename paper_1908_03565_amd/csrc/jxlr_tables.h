@@ -6,8 +6,8 @@
 
 namespace jxlr {
 
-// Number of transform types the library reconstructs (C.5.4 values 0..11).
-constexpr int kNumStrategies = 12;
+// Number of transform types the library reconstructs (C.5.4 values 0..14).
+constexpr int kNumStrategies = 15;
 
 // Varblock size in 8x8 blocks of transform type s (I.2.5: "DCT N x M" is
 // max(8, N) wide and max(8, M) tall).
@@ -30,7 +30,7 @@ int dq_offset(int s);
 constexpr int kSrgbBucket0 = (127 - 14) << 7;
 constexpr int kSrgbBuckets = (127 << 7) - kSrgbBucket0 + 1;
 constexpr int kSrgbBucketsPadded = (kSrgbBuckets + 3) & ~3;
-constexpr int kDqFloats = 3 * (4 * 64 + 256 + 1024 + 2 * 128 + 2 * 256 + 2 * 512);
+constexpr int kDqFloats = 3 * (4 * 64 + 256 + 1024 + 2 * 128 + 2 * 256 + 2 * 512 + 3 * 64);
 
 // Everything the kernels read that does not depend on the frame.  One
 // instance lives in device memory per context.
@@ -80,6 +80,8 @@ struct DeviceTables {
   // A-operand order of a 32x32x16 matrix instruction: element e of lane l in
   // k-step t is A[l mod 32][16 t + 8 (l / 32) + e].
   alignas(16) uint16_t mfma_a[3][2][2][64][8];
+  // AFV basis (I.2.2): afv[j][i] = basis vector j at 4x4 index i.
+  float afv[16][16];
 };
 
 // Fills t on the host.  Returns false if a dequantization matrix entry is not

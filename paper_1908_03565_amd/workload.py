@@ -29,13 +29,17 @@ import numpy as np
 # Transform types by their C.5.4 numbers.
 DCT8, IDENTITY, DCT2, DCT4, DCT16, DCT32 = 0, 1, 2, 3, 4, 5
 DCT16X8, DCT8X16, DCT32X8, DCT8X32, DCT32X16, DCT16X32 = 6, 7, 8, 9, 10, 11
+DCT4X8, DCT8X4, AFV = 12, 13, 14
 
 # Varblock size in 8x8 blocks, (columns, rows), of each transform type.
 BLOCKS = {0: (1, 1), 1: (1, 1), 2: (1, 1), 3: (1, 1), 4: (2, 2), 5: (4, 4),
-          6: (2, 1), 7: (1, 2), 8: (4, 1), 9: (1, 4), 10: (4, 2), 11: (2, 4)}
+          6: (2, 1), 7: (1, 2), 8: (4, 1), 9: (1, 4), 10: (4, 2), 11: (2, 4),
+          12: (1, 1), 13: (1, 1), 14: (1, 1)}
 
 # The ten transform types the mixed workloads draw from.
 MIXED = [DCT8, DCT4, DCT2, IDENTITY, DCT16, DCT32, DCT8X16, DCT16X8, DCT16X32, DCT32X16]
+# Every C.5.4 type (test frames beyond the workloads).
+ALL_TYPES = list(range(15))
 
 # Frame-parameter overrides common to every workload: global_scale = 65536 so
 # that AcMul = 1 / QF, in [1/32, 1] for QF in [1, 32]; DC multipliers that give

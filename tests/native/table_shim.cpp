@@ -29,4 +29,5 @@ const float* shim_thr(int bits) { return bits == 8 ? g_tables.srgb_thr8 : g_tabl
 const uint8_t* shim_start8() { return g_tables.srgb_start8; }
 int shim_bucket0() { return jxlr::kSrgbBucket0; }
 int shim_buckets() { return jxlr::kSrgbBuckets; }
+const float* shim_afv() { return &g_tables.afv[0][0]; }
 }

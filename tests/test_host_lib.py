@@ -65,7 +65,7 @@ def test_validate_maps_host():
     p24 = J.params(24, 24)
     f = _frame(24, 24); f["strategy"][2, 2] = 4
     assert J.validate_maps_host(p24, f) == 4  # out of bounds
-    for bad in (12, 13, 14, 15, 200):
+    for bad in (15, 16, 200):
         f = _frame(); f["strategy"][3, 3] = bad
         assert J.validate_maps_host(p, f) == 3
     f = _frame(s=4); f["qf"][1, 1] = 5
@@ -127,6 +127,7 @@ def shim(tmp_path_factory):
     L.shim_thr.restype = C.POINTER(C.c_float)
     L.shim_mfma.restype = C.POINTER(C.c_uint16)
     L.shim_start8.restype = C.POINTER(C.c_uint8)
+    L.shim_afv.restype = C.POINTER(C.c_float)
     assert L.shim_build() == 1
     return L
 
@@ -135,16 +136,24 @@ def _arr(ptr, n):
     return np.ctypeslib.as_array(ptr, shape=(n,)).copy()
 
 
+DQ_FLOATS = 3 * (4 * 64 + 256 + 1024 + 2 * 128 + 2 * 256 + 2 * 512 + 3 * 64)
+
+
 def test_dequant_tables_match_oracle(shim):
-    for s in range(12):
+    for s in range(15):
         bx, by = O.varblock_size(s)
         for c in range(3):
             buf = np.zeros(bx * by)
             assert shim.shim_dequant(s, c, buf.ctypes.data_as(C.POINTER(C.c_double))) == 1
             ref = O.dequant_matrix(s, c).ravel()
             np.testing.assert_allclose(buf[1:], ref[1:], rtol=1e-12, err_msg=f"{s},{c}")
-            f32 = _arr(shim.shim_dq(), 9984)[shim.shim_dq_offset(s) + c * bx * by:][:bx * by]
+            f32 = _arr(shim.shim_dq(), DQ_FLOATS)[shim.shim_dq_offset(s) + c * bx * by:][:bx * by]
             np.testing.assert_allclose(f32[1:], ref[1:], rtol=1e-7)
+
+
+def test_afv_basis_matches_oracle(shim):
+    np.testing.assert_allclose(_arr(shim.shim_afv(), 256).reshape(16, 16), O.afv_basis(),
+                               rtol=0, atol=6e-8)
 
 
 def test_transform_tables_match_oracle(shim):
@@ -192,13 +201,17 @@ def _col_scale(n):
 def test_prescaled_tables_match_oracle(shim):
     # dqs = dq times the scales that turn the draft's inverse into the plain
     # DCT-III the kernels run; likewise a16s/a32s on the output frequency.
-    dqs = _arr(shim.shim_dqs(), 9984)
-    for s in range(12):
+    dqs = _arr(shim.shim_dqs(), DQ_FLOATS)
+    for s in range(15):
         bx, by = O.varblock_size(s)
+        s4, s8, half = _col_scale(4), _col_scale(8), np.arange(8) // 2
         if s == 3:
-            s4 = _col_scale(4)
-            sc = np.outer(s4[np.arange(8) // 2], s4[np.arange(8) // 2])
-        elif s in (1, 2):
+            sc = np.outer(s4[half], s4[half])
+        elif s == 12:  # rows: interleaved 4-point, columns: 8-point
+            sc = np.outer(s4[half], s8)
+        elif s == 13:
+            sc = np.outer(s8, s4[half])
+        elif s in (1, 2, 14):
             sc = np.ones((8, 8))
         else:
             sc = np.outer(_col_scale(by), _col_scale(bx))
