@@ -242,7 +242,7 @@ def bench_frame(args, J, wl, torch, np):
             # flip-affected ones
             names = {0: "DCT8", 1: "IDENTITY", 2: "DCT2", 3: "DCT4", 4: "DCT16", 5: "DCT32",
                      6: "DCT16X8", 7: "DCT8X16", 8: "DCT32X8", 9: "DCT8X32", 10: "DCT32X16",
-                     11: "DCT16X32"}
+                     11: "DCT16X32", 12: "DCT4X8", 13: "DCT8X4", 14: "AFV"}
             per_type = {names[t]: v for t, v in P.max_err_by_type(frame, gpu, orc, cmp["mask"]).items()}
             tol = 1e-3 if args.split else P.RGB_TOL
             err = dict(max_abs_err=cmp["max_err"], tol=tol,
@@ -555,7 +555,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c1x1024", "c5"])
+    ap.add_argument("--workload", default="c2",
+                    choices=["c1", "c2", "c2t", "c3", "c4", "c1x1024", "c5"])
     ap.add_argument("--no-check", action="store_true", help="skip the oracle comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,

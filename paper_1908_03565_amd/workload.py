@@ -166,6 +166,14 @@ def c2():
     return frame(2048, 2048, seed=2, epf_iters=2, gab=1, name="c2_2048x2048_mixed_epf2")
 
 
+def c2t():
+    """The 2048x2048 recipe with regions drawn from every C.5.4 type except
+    DCT32x8 / DCT8x32 (whose default tables drive samples out of range)."""
+    types = [t for t in ALL_TYPES if t not in (DCT32X8, DCT8X32)]
+    return frame(2048, 2048, seed=2, choices=types, epf_iters=2, gab=1,
+                 name="c2t_2048x2048_13types_epf2")
+
+
 def c3():
     return frame(4096, 4096, seed=3, p_dct32=0.5, epf_iters=2, gab=1,
                  name="c3_4096x4096_half_dct32")
