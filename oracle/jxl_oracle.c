@@ -891,6 +891,36 @@ static int check_params(const orc_params* p) {
   return ORC_OK;
 }
 
+/* F.2 adaptive DC smoothing of the dequantized DC image, per channel, in
+ * place: every sample away from the first and last row and column becomes the
+ * 3x3 weighted average of the unsmoothed samples (centre 0.05226273532324128,
+ * edge neighbours 0.20345139757231578, diagonal ones 0.0334829185968739) when
+ * that average lies within 0.5 dcq of the sample, else keeps its value.
+ * Readings: dcq is the channel's DC multiplier divided by 2^extra_levels (the
+ * DcQuantField of C.5.2 for a zero decoded delta, and the multiplier itself
+ * when extra_levels is 0); the smoothing precedes the DC chroma from luma. */
+void orc_dc_smooth(const orc_params* p, int32_t Wb, int32_t Hb, double* dcq) {
+  const double wc = 0.05226273532324128, we = 0.20345139757231578, wd = 0.0334829185968739;
+  double* src = (double*)malloc(sizeof(double) * Wb * Hb);
+  if (!src) return;
+  for (int c = 0; c < 3; ++c) {
+    double* d = dcq + (size_t)c * Wb * Hb;
+    memcpy(src, d, sizeof(double) * Wb * Hb);
+    const double q = p->dc_mul[c] / (double)(1 << p->extra_levels[c]);
+    for (int32_t y = 1; y + 1 < Hb; ++y)
+      for (int32_t x = 1; x + 1 < Wb; ++x) {
+        const double* r0 = src + (size_t)(y - 1) * Wb + x;
+        const double* r1 = src + (size_t)y * Wb + x;
+        const double* r2 = src + (size_t)(y + 1) * Wb + x;
+        const double s = r1[0];
+        const double wa = wc * s + we * (r0[0] + r1[-1] + r1[1] + r2[0]) +
+                          wd * (r0[-1] + r0[1] + r2[-1] + r2[1]);
+        if (s - 0.5 * q <= wa && wa <= s + 0.5 * q) d[(size_t)y * Wb + x] = wa;
+      }
+  }
+  free(src);
+}
+
 int orc_reconstruct(const orc_params* p, const int32_t* const ac[3], const int32_t* const dc[3],
                     const uint8_t* strategy, const uint8_t* qf_minus_1, const float* cfl_kx,
                     const float* cfl_kb, double* xyb) {
@@ -918,6 +948,7 @@ int orc_reconstruct(const orc_params* p, const int32_t* const ac[3], const int32
   for (int c = 0; c < 3; ++c)
     for (int32_t i = 0; i < Wb * Hb; ++i)
       dcq[c * Wb * Hb + i] = p->dc_mul[c] * dc[c][i] / (double)(1 << p->extra_levels[c]);
+  if (p->dc_smoothing) orc_dc_smooth(p, Wb, Hb, dcq);
   for (int32_t i = 0; i < Wb * Hb; ++i) {
     double Y = dcq[1 * Wb * Hb + i];
     dcq[0 * Wb * Hb + i] += p->kx_dc * Y;

@@ -71,6 +71,7 @@ typedef struct {
   double  opsin_inv[9];        /* inverse opsin absorbance matrix, row-major (L.2) */
   double  opsin_bias[3];
   int32_t target_nits_div50;   /* ImageMetadata (A.4.5) */
+  int32_t dc_smoothing;        /* adaptive DC smoothing of F.2; 0 = skipped */
 } orc_params;
 
 /* Fills the defaults the draft gives for every field (C.4, C.10, L.2, A.4.5). */
@@ -108,6 +109,8 @@ int orc_dequant_matrix(int strategy, int c, double* out);
 /* ---- reconstruction (F, G, I) ------------------------------------------ */
 /* Quantized DC/AC planes and side maps -> XYB samples, cropped to xsize x ysize.
  * cfl_kx/cfl_kb: per 64x64 tile kX and kB of Annex G, [ceil(ysize/64)][ceil(xsize/64)]. */
+/* F.2 adaptive DC smoothing of a dequantized DC image [3][Hb][Wb], in place. */
+void orc_dc_smooth(const orc_params* p, int32_t Wb, int32_t Hb, double* dcq);
 int orc_reconstruct(const orc_params* p,
                     const int32_t* const ac[3], const int32_t* const dc[3],
                     const uint8_t* strategy, const uint8_t* qf_minus_1,

@@ -34,6 +34,7 @@ class OrcParams(C.Structure):
         ("opsin_inv", C.c_double * 9),
         ("opsin_bias", C.c_double * 3),
         ("target_nits_div50", C.c_int32),
+        ("dc_smoothing", C.c_int32),
     ]
 
 
@@ -66,6 +67,7 @@ def lib():
         L.orc_dc_from_llf.argtypes = [C.c_int, _f64p, _f64p]
         L.orc_dequant_matrix.argtypes = [C.c_int, C.c_int, _f64p]
         L.orc_afv_basis.argtypes = [_f64p]
+        L.orc_dc_smooth.argtypes = [P, C.c_int32, C.c_int32, _f64p]
         ptr3 = C.c_void_p * 3
         L.orc_reconstruct.argtypes = [P, ptr3, ptr3, _u8p, _u8p, _f32p, _f32p, _f64p]
         L.orc_epf_mul_table.argtypes = [C.c_int32, _i32p]
@@ -181,6 +183,13 @@ def dc_from_llf(s, llf):
     out = np.zeros((cy, cx))
     _check(lib().orc_dc_from_llf(s, L, out))
     return out
+
+
+def dc_smooth(p, dcq):
+    """F.2 adaptive DC smoothing of a dequantized DC image (3, Hb, Wb)."""
+    d = np.array(dcq, dtype=np.float64, order="C", copy=True)
+    lib().orc_dc_smooth(C.byref(p), d.shape[2], d.shape[1], d)
+    return d
 
 
 def afv_basis():

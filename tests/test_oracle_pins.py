@@ -570,6 +570,63 @@ def test_ill_formed_maps_are_rejected():
 
 
 # --------------------------------------------------------------------------
+# Adaptive DC smoothing (F.2)
+# --------------------------------------------------------------------------
+
+# The 3x3 weights as printed (centre, edge neighbours, diagonal neighbours).
+DC_SMOOTH_W = (0.05226273532324128, 0.20345139757231578, 0.0334829185968739)
+
+
+def test_dc_smoothing_keeps_affine_images_and_borders():
+    # the stencil is symmetric and its weights sum to one, so an affine DC
+    # image is a fixed point; first/last rows and columns are never touched
+    Hb, Wb = 9, 13
+    y, x = np.mgrid[0:Hb, 0:Wb].astype(np.float64)
+    d = np.stack([0.3 + 0.01 * x - 0.02 * y, -0.5 + 0.003 * x, 0.25 * y - 0.125 * x])
+    p = O.params(8 * Wb, 8 * Hb, dc_mul=(1.0, 1.0, 1.0), dc_smoothing=1)
+    out = O.dc_smooth(p, d)
+    np.testing.assert_allclose(out, d, atol=1e-14)
+    noisy = d + _rng(5).standard_normal(d.shape) * 0.01
+    out = O.dc_smooth(p, noisy)
+    np.testing.assert_array_equal(out[:, 0, :], noisy[:, 0, :])
+    np.testing.assert_array_equal(out[:, -1, :], noisy[:, -1, :])
+    np.testing.assert_array_equal(out[:, :, 0], noisy[:, :, 0])
+    np.testing.assert_array_equal(out[:, :, -1], noisy[:, :, -1])
+
+
+def test_dc_smoothing_is_the_weighted_average_when_close():
+    # variations well inside 0.5 dcq: every interior sample takes the 3x3
+    # weighted average (scipy's correlation with the printed weights)
+    from scipy import ndimage
+    wc, we, wd = DC_SMOOTH_W
+    k = np.array([[wd, we, wd], [we, wc, we], [wd, we, wd]])
+    d = _rng(6).standard_normal((3, 10, 12)) * 0.05
+    p = O.params(96, 80, dc_mul=(2.0, 3.0, 4.0), dc_smoothing=1)
+    out = O.dc_smooth(p, d)
+    for c in range(3):
+        ref = ndimage.correlate(d[c], k, mode="nearest")
+        np.testing.assert_allclose(out[c, 1:-1, 1:-1], ref[1:-1, 1:-1], atol=1e-14)
+
+
+def test_dc_smoothing_keeps_samples_far_from_the_average():
+    # a checkerboard of amplitude 4 dcq: every average is far from its sample
+    # (by 4 dcq (1 - wc + 4 we - 4 wd), about 6.5 dcq), so nothing changes
+    y, x = np.mgrid[0:8, 0:8]
+    d = np.stack([np.where((x + y) % 2 == 0, 4.0, -4.0) * q for q in (1.0, 0.5, 2.0)])
+    p = O.params(64, 64, dc_mul=(1.0, 0.5, 2.0), dc_smoothing=1)
+    np.testing.assert_array_equal(O.dc_smooth(p, d), d)
+    # dcq follows extra_levels: dividing the multiplier by 2^levels narrows the
+    # window, so a nearly flat image with a 0.3-high bump at dcq = 1 is
+    # smoothed there, and left alone at dcq = 1/4
+    d = np.zeros((3, 6, 6))
+    d[:, 3, 3] = 0.3
+    p1 = O.params(48, 48, dc_mul=(1.0, 1.0, 1.0), dc_smoothing=1)
+    p4 = O.params(48, 48, dc_mul=(1.0, 1.0, 1.0), extra_levels=(2, 2, 2), dc_smoothing=1)
+    assert O.dc_smooth(p1, d)[0, 3, 3] < 0.3
+    assert O.dc_smooth(p4, d)[0, 3, 3] == 0.3
+
+
+# --------------------------------------------------------------------------
 # Gaborish (J.4)
 # --------------------------------------------------------------------------
 
