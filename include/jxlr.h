@@ -101,6 +101,14 @@ typedef struct {
    * high and low parts, hi*hi + hi*lo + lo*hi accumulated in binary32; other
    * regions use the plain form. */
   int32_t  idct_split;
+  /* Adaptive DC smoothing of F.2 (1) or not (0, the default; the draft's
+   * kSkipAdaptiveDCSmoothing case): each dequantized DC sample away from the
+   * frame's first and last block row and column becomes the 3x3 weighted
+   * average of its neighbourhood when that lies within 0.5 dcq of it, dcq =
+   * dc_mul[c] (the DcQuantField of C.5.2 with extra_levels 0, which smoothing
+   * therefore requires: JXLR_E_PARAM otherwise).  Applied before the DC chroma
+   * from luma and the LLF computation. */
+  int32_t  dc_smoothing;
 } jxlr_frame_params;
 
 /* Input and output planes of one frame.  With Wb = ceil(xsize/8),

@@ -293,6 +293,7 @@ struct ReconArgs {
   int* status;
   const DeviceTables* __restrict__ tab;
   int split;        // split-precision matrix-core transform of uniform regions
+  int dc_smooth;    // adaptive DC smoothing (F.2); dcq = dc_mul
   int ac_vec;       // AC planes and stride allow 16-byte loads
   int xyb_vec;      // XYB planes and stride allow 16-byte stores
 };
@@ -549,7 +550,25 @@ __device__ __attribute__((always_inline)) inline void recon_tile(const ReconArgs
     const size_t d = in ? size_t(by) * a.dc_stride + bx : 0;
     const float dv0 = float(a.dc[0][d]), dv1 = float(a.dc[1][d]), dv2 = float(a.dc[2][d]);
     const float qfv = float(1 + a.qf[m]);
-    const float x_ = a.dc_mul[0] * dv0, y_ = a.dc_mul[1] * dv1, b_ = a.dc_mul[2] * dv2;
+    float x_ = a.dc_mul[0] * dv0, y_ = a.dc_mul[1] * dv1, b_ = a.dc_mul[2] * dv2;
+    if (a.dc_smooth && in && bx > 0 && by > 0 && bx + 1 < a.Wb && by + 1 < a.Hb) {
+      // F.2 adaptive smoothing of the dequantized DC, per channel, from the
+      // unsmoothed 3x3 neighbourhood (read from the planes: it may leave the
+      // tile)
+      float* v[3] = {&x_, &y_, &b_};
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const int32_t* p0 = a.dc[c] + d - a.dc_stride;
+        const int32_t* p1 = a.dc[c] + d;
+        const int32_t* p2 = a.dc[c] + d + a.dc_stride;
+        const float e = float(p0[0]) + float(p1[-1]) + float(p1[1]) + float(p2[0]);
+        const float g = float(p0[-1]) + float(p0[1]) + float(p2[-1]) + float(p2[1]);
+        const float sv = *v[c], q = a.dc_mul[c];
+        const float wa = fmaf(0.05226273532324128f, sv,
+                              q * fmaf(0.20345139757231578f, e, 0.0334829185968739f * g));
+        if (sv - 0.5f * q <= wa && wa <= sv + 0.5f * q) *v[c] = wa;
+      }
+    }
     // C.5.5: AcMul = 2^16 / (global_scale * (1 + dv)); the product is an
     // integer below 2^24, so one rounding.
     s_acmul[tid] = in ? 65536.0f / (a.gscale * qfv) : 0.0f;
@@ -1475,6 +1494,10 @@ jxlr_status check_params(const jxlr_frame_params* p) {
   if (p->target_nits_div50 < 1) return JXLR_E_PARAM;
   if (p->out_format < JXLR_OUT_F32 || p->out_format > JXLR_OUT_U16_SRGB) return JXLR_E_PARAM;
   if (p->idct_split < 0 || p->idct_split > 1) return JXLR_E_PARAM;
+  if (p->dc_smoothing < 0 || p->dc_smoothing > 1) return JXLR_E_PARAM;
+  if (p->dc_smoothing &&
+      (p->extra_levels[0] != 0 || p->extra_levels[1] != 0 || p->extra_levels[2] != 0))
+    return JXLR_E_PARAM;
   return JXLR_OK;
 }
 
@@ -1682,6 +1705,7 @@ jxlr_status make_recon_args(jxlr_ctx* ctx, const jxlr_frame_params* p, const jxl
   a.status = ctx->status;
   a.tab = ctx->tables;
   a.split = p->idct_split;
+  a.dc_smooth = p->dc_smoothing;
   {
     bool av = (io->ac_stride & 3) == 0;
     for (int c = 0; c < 3; ++c) av = av && (reinterpret_cast<uintptr_t>(io->ac[c]) & 15) == 0;

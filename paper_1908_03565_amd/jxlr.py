@@ -40,6 +40,7 @@ class FrameParams(C.Structure):
         ("target_nits_div50", C.c_int32),
         ("out_format", C.c_int32),
         ("idct_split", C.c_int32),
+        ("dc_smoothing", C.c_int32),
     ]
 
 

@@ -101,6 +101,36 @@ def test_all_types_end_to_end(ctx):
     assert cmp["affected"] <= 0.05 * cmp["pixels"]
 
 
+@pytest.mark.parametrize("W,H,seed", [(192, 136, 21), (131, 77, 22)])
+def test_dc_smoothing_end_to_end(ctx, W, H, seed):
+    # F.2 adaptive DC smoothing on, against the oracle with it on; DC values
+    # spread over a few dcq so that both outcomes of the window test occur
+    f = wl.small(W, H, seed=seed)
+    rng = np.random.default_rng(seed)
+    Hb, Wb = (H + 7) // 8, (W + 7) // 8
+    f["dc"] = (rng.integers(-2, 3, size=(3, Hb, Wb)) * rng.integers(0, 2, size=(3, Hb, Wb))
+               + rng.integers(-512, 513, size=(3, 1, 1)) // 64).astype(np.int32)
+    # The window test |wa - s| <= 0.5 dcq reads, in units of dcq, as a test
+    # on the integers; no sample of these frames is within 1e-3 of its
+    # boundary, so binary32 and binary64 take the same decisions.
+    wc, we, wd = 0.05226273532324128, 0.20345139757231578, 0.0334829185968739
+    d = f["dc"].astype(np.float64)
+    n = d[:, 1:-1, 1:-1]
+    e = d[:, :-2, 1:-1] + d[:, 2:, 1:-1] + d[:, 1:-1, :-2] + d[:, 1:-1, 2:]
+    g = d[:, :-2, :-2] + d[:, :-2, 2:] + d[:, 2:, :-2] + d[:, 2:, 2:]
+    assert np.abs(np.abs(we * e + wd * g - (1 - wc) * n) - 0.5).min() > 1e-3
+    p, q, gpu, orc = _run(ctx, f, dc_smoothing=1)
+    ok, err = xyb_err_ok(gpu["recon"], orc["recon"])
+    assert ok, err
+    cmp = P.compare_rgb(p, gpu, orc)
+    print(cmp)
+    assert cmp["max_err"] <= P.RGB_TOL
+    # the flag is honoured: without it the reconstruction differs
+    p0, q0, gpu0, orc0 = _run(ctx, f)
+    assert np.abs(orc0["recon"] - orc["recon"]).max() > 1e-5
+    assert np.abs(gpu0["recon"] - gpu["recon"]).max() > 1e-5
+
+
 @pytest.mark.parametrize("seed", [11, 12])
 def test_mixed_small_end_to_end(ctx, seed):
     f = wl.small(192, 136, seed=seed)

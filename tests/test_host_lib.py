@@ -79,13 +79,17 @@ def test_validate_maps_host():
 def test_parameter_ranges():
     f = _frame()
     for k, v in [("epf_weight_min", 1.5), ("epf_sigma_max", 700), ("epf_sigma_shift", 9),
-                 ("idct_split", 2), ("idct_split", -1),
+                 ("idct_split", 2), ("idct_split", -1), ("dc_smoothing", 2),
                  ("epf_iters", 4), ("global_scale", 0), ("target_nits_div50", 0),
                  ("out_format", 3)]:
         p = J.params(64, 64, **{k: v})
         assert J.validate_maps_host(p, f) == 7, k
         assert J.workspace_bytes(p) == 0
     assert J.validate_maps_host(J.params(0, 8), _frame(8, 8)) == 2
+    # smoothing takes dcq from the DC multipliers, which needs extra_levels 0
+    p = J.params(64, 64, dc_smoothing=1, extra_levels=(0, 1, 0))
+    assert J.validate_maps_host(p, f) == 7
+    assert J.validate_maps_host(J.params(64, 64, dc_smoothing=1), f) == 0
 
 
 def test_workspace_bytes():
