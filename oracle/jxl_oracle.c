@@ -73,6 +73,8 @@ void orc_params_default(orc_params* p, int32_t xsize, int32_t ysize) {
   p->opsin_bias[1] = -0.00100549;
   p->opsin_bias[2] = -0.00094081;
   p->target_nits_div50 = 5;  /* A.4.5 */
+  p->qco = 0;                 /* C.10: qco defaults to false */
+  p->qco_interval_mul = 0.5;
 }
 
 int orc_num_threads(void) {
@@ -1218,6 +1220,109 @@ int orc_epf_pass(const orc_params* p, const uint8_t* strategy, const uint8_t* qf
 }
 
 /* ======================================================================= */
+/* Quantization constraint (J.3)                                           */
+/* ======================================================================= */
+
+/* The forward transforms of I.2.3 are unnormalized: followed by the inverse
+ * transform of I.2.4 they give the samples times this gain (the number of
+ * samples for the DCT family, 16 for DCT4 with its 4 x 4 sub-blocks, 32 for
+ * the 4 x 8 halves of DCT4x8 and DCT8x4, 1 for the other types). */
+static double forward_gain(int s, int32_t bx, int32_t by) {
+  if (is_dct_family(s)) return (double)(bx * by);
+  if (s == ORC_DCT4) return 16.0;
+  if (s == ORC_DCT4X8 || s == ORC_DCT8X4) return 32.0;
+  return 1.0;
+}
+
+/* For every varblock and channel: the residual filt - orig over the
+ * varblock's samples goes through the varblock's forward transform (I.2.3,
+ * divided by its gain, so that the coefficients are in the units of the
+ * dequantized coefficients that I.2.4 maps back to samples);
+ * its LLF corner is turned into DC samples (I.2.6); every DC sample and every
+ * other coefficient is clamped to qco_interval_mul times its quantization
+ * step on either side of 0; the DC samples go back to the LLF corner (I.2.7)
+ * and the inverse transform (I.2.4) gives the residual that is added to
+ * orig.  Readings:
+ *   - the step of a coefficient outside the LLF corner is its dequantization
+ *     matrix entry times AcMul (the factor F.3 multiplies a quantized value
+ *     by), of a DC sample the DC multiplier over 2^extra_levels (the
+ *     DcQuantField of C.5.2 for a zero decoded delta);
+ *   - samples of a varblock outside the frame were never filtered: their
+ *     residual is 0, and only samples inside the frame are written;
+ *   - the clamp acts on each channel's own coefficients (chroma from luma
+ *     plays no part). */
+int orc_qco(const orc_params* p, const uint8_t* strategy, const uint8_t* qf_minus_1,
+            const double* orig, const double* filt, double* out) {
+  int st = check_params(p);
+  if (st) return st;
+  if (!(p->qco_interval_mul >= 0.0)) return ORC_E_PARAM;
+  const int32_t W = p->xsize, H = p->ysize;
+  const int32_t Wb = (W + 7) / 8, Hb = (H + 7) / 8;
+  double (*dq)[3][1024] = (double (*)[3][1024])malloc(sizeof(double) * 15 * 3 * 1024);
+  varblock* list = (varblock*)malloc(sizeof(varblock) * Wb * Hb);
+  if (!dq || !list) { free(dq); free(list); return ORC_E_SIZE; }
+  for (int s = 0; s < 15 && !st; ++s)
+    for (int c = 0; c < 3 && !st; ++c) st = orc_dequant_matrix(s, c, dq[s][c]);
+  int32_t nvb = 0;
+  if (!st) st = scan_varblocks(Wb, Hb, strategy, list, &nvb, NULL);
+  if (st) { free(dq); free(list); return st; }
+  memcpy(out, filt, sizeof(double) * 3 * (size_t)W * H);
+  const double m = p->qco_interval_mul;
+
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int32_t v = 0; v < nvb; ++v) {
+    const varblock vb = list[v];
+    int32_t bx, by;
+    orc_varblock_size(vb.s, &bx, &by);
+    /* the LLF corner: cx x cy for the DCT family, the single (0, 0) otherwise */
+    int32_t cx = bx / 8, cy = by / 8;
+    if (!is_dct_family(vb.s)) cx = cy = 1;
+    const double acmul =
+        65536.0 / ((double)p->global_scale * (1.0 + qf_minus_1[vb.by0 * Wb + vb.bx0]));
+    for (int c = 0; c < 3; ++c) {
+      const size_t pl = (size_t)c * W * H;
+      double R[1024], K[1024], S[1024], L[16], D[16];
+      for (int32_t y = 0; y < by; ++y)
+        for (int32_t x = 0; x < bx; ++x) {
+          const int32_t gx = 8 * vb.bx0 + x, gy = 8 * vb.by0 + y;
+          R[y * bx + x] =
+              (gx < W && gy < H) ? filt[pl + (size_t)gy * W + gx] - orig[pl + (size_t)gy * W + gx]
+                                 : 0.0;
+        }
+      orc_forward_transform(vb.s, R, K);
+      const double g = forward_gain(vb.s, bx, by);
+      for (int32_t y = 0; y < by; ++y)
+        for (int32_t x = 0; x < bx; ++x) {
+          const int32_t k = y * bx + x;
+          K[k] /= g;
+          if (x < cx && y < cy) {
+            L[y * cx + x] = K[k];
+          } else {
+            const double t = m * dq[vb.s][c][k] * acmul;
+            K[k] = fmin(fmax(K[k], -t), t);
+          }
+        }
+      orc_dc_from_llf(vb.s, L, D);
+      const double tq = m * p->dc_mul[c] / (double)(1 << p->extra_levels[c]);
+      for (int32_t i = 0; i < cx * cy; ++i) D[i] = fmin(fmax(D[i], -tq), tq);
+      orc_llf_from_dc(vb.s, D, L);
+      for (int32_t y = 0; y < cy; ++y)
+        for (int32_t x = 0; x < cx; ++x) K[y * bx + x] = L[y * cx + x];
+      orc_inverse_transform(vb.s, K, S);
+      for (int32_t y = 0; y < by; ++y)
+        for (int32_t x = 0; x < bx; ++x) {
+          const int32_t gx = 8 * vb.bx0 + x, gy = 8 * vb.by0 + y;
+          if (gx < W && gy < H)
+            out[pl + (size_t)gy * W + gx] = orig[pl + (size_t)gy * W + gx] + S[y * bx + x];
+        }
+    }
+  }
+  free(dq);
+  free(list);
+  return ORC_OK;
+}
+
+/* ======================================================================= */
 /* Gaborish (J.4)                                                          */
 /* ======================================================================= */
 
@@ -1306,10 +1411,22 @@ int orc_decode(const orc_params* p, const int32_t* const ac[3], const int32_t* c
   double* b = (double*)malloc(sizeof(double) * n);
   if (!a || !b) { free(a); free(b); return ORC_E_SIZE; }
   st = orc_reconstruct(p, ac, dc, strategy, qf_minus_1, cfl_kx, cfl_kb, a);
+  double* r = NULL;
+  if (!st && p->qco && p->epf_iters > 0) {
+    r = (double*)malloc(sizeof(double) * n);
+    if (!r) st = ORC_E_SIZE;
+    else memcpy(r, a, sizeof(double) * n);
+  }
   for (int it = 0; !st && it < p->epf_iters; ++it) {
     st = orc_epf_pass(p, strategy, qf_minus_1, sharpness, a, b, NULL, NULL);
     double* t = a; a = b; b = t;
   }
+  /* J.1: the constraint follows the filter passes, against their input */
+  if (!st && r) {
+    st = orc_qco(p, strategy, qf_minus_1, r, a, b);
+    double* t = a; a = b; b = t;
+  }
+  free(r);
   if (!st && p->gab) {
     st = orc_gaborish(p, a, b);
     double* t = a; a = b; b = t;

@@ -72,6 +72,8 @@ typedef struct {
   double  opsin_bias[3];
   int32_t target_nits_div50;   /* ImageMetadata (A.4.5) */
   int32_t dc_smoothing;        /* adaptive DC smoothing of F.2; 0 = skipped */
+  int32_t qco;                 /* loop_filter.qco (C.10): J.3 after the EPF passes */
+  double  qco_interval_mul;    /* loop_filter.qco_interval_mul (C.10) */
 } orc_params;
 
 /* Fills the defaults the draft gives for every field (C.4, C.10, L.2, A.4.5). */
@@ -128,6 +130,11 @@ int orc_epf_pass(const orc_params* p, const uint8_t* strategy,
                  const uint8_t* qf_minus_1, const uint8_t* sharpness,
                  const double* in, double* out,
                  uint8_t* guide_out, int32_t* sigma_out);
+/* Quantization constraint (J.3): orig is the input of the first filter
+ * pass, filt the output of the last, out receives the constrained frame
+ * (all [3][ysize][xsize]; out may not alias orig). */
+int orc_qco(const orc_params* p, const uint8_t* strategy, const uint8_t* qf_minus_1,
+            const double* orig, const double* filt, double* out);
 /* Gaborish (J.4). */
 int orc_gaborish(const orc_params* p, const double* in, double* out);
 
@@ -138,7 +145,8 @@ int orc_xyb_to_rgb(const orc_params* p, const double* xyb, double* rgb);
 int orc_quantize_srgb(int32_t bits, int64_t n, const double* lin, uint16_t* out);
 
 /* ---- whole path -------------------------------------------------------- */
-/* Reconstruct, epf_iters EPF passes, Gaborish (if p->gab), XYB -> RGB.
+/* Reconstruct, epf_iters EPF passes, the quantization constraint (if p->qco
+ * and at least one pass), Gaborish (if p->gab), XYB -> RGB.
  * rgb: [3][ysize][xsize] of [0,1]-scaled linear RGB. */
 int orc_decode(const orc_params* p,
                const int32_t* const ac[3], const int32_t* const dc[3],

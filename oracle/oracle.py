@@ -35,6 +35,8 @@ class OrcParams(C.Structure):
         ("opsin_bias", C.c_double * 3),
         ("target_nits_div50", C.c_int32),
         ("dc_smoothing", C.c_int32),
+        ("qco", C.c_int32),
+        ("qco_interval_mul", C.c_double),
     ]
 
 
@@ -74,6 +76,7 @@ def lib():
         L.orc_epf_weight.argtypes = [C.c_int32, C.c_int32]
         L.orc_epf_weight.restype = C.c_float
         L.orc_epf_pass.argtypes = [P, _u8p, _u8p, _u8p, _f64p, _f64p, C.c_void_p, C.c_void_p]
+        L.orc_qco.argtypes = [P, _u8p, _u8p, _f64p, _f64p, _f64p]
         L.orc_gaborish.argtypes = [P, _f64p, _f64p]
         L.orc_xyb_to_rgb.argtypes = [P, _f64p, _f64p]
         L.orc_quantize_srgb.argtypes = [C.c_int32, C.c_int64, _f64p, _u16p]
@@ -254,6 +257,18 @@ def epf_pass(p, frame, xyb, want_debug=False):
     return out
 
 
+def qco(p, frame, orig, filt):
+    """J.3 quantization constraint: orig is the input of the first EPF pass,
+    filt the output of the last; returns the constrained frame."""
+    orig = np.ascontiguousarray(orig, dtype=np.float64)
+    filt = np.ascontiguousarray(filt, dtype=np.float64)
+    out = np.zeros_like(filt)
+    _check(lib().orc_qco(
+        C.byref(p), np.ascontiguousarray(frame["strategy"], np.uint8),
+        np.ascontiguousarray(frame["qf"], np.uint8), orig, filt, out))
+    return out
+
+
 def gaborish(p, xyb):
     xyb = np.ascontiguousarray(xyb, dtype=np.float64)
     out = np.zeros_like(xyb)
@@ -291,13 +306,17 @@ def decode(p, frame):
 
 def decode_stages(p, frame):
     """Whole path with every intermediate kept (for stage-by-stage comparison).
-    Returns dict: recon, epf (list of (out, guide, sigma)), gab, rgb."""
+    Returns dict: recon, epf (list of (out, guide, sigma)), qco (when
+    applied), gab, rgb."""
     res = {"recon": reconstruct(p, frame), "epf": []}
     cur = res["recon"]
     for _ in range(p.epf_iters):
         out, g, s = epf_pass(p, frame, cur, want_debug=True)
         res["epf"].append((out, g, s))
         cur = out
+    if p.qco and p.epf_iters > 0:
+        cur = qco(p, frame, res["recon"], cur)
+        res["qco"] = cur
     if p.gab:
         cur = gaborish(p, cur)
     res["gab"] = cur

@@ -627,6 +627,138 @@ def test_dc_smoothing_keeps_samples_far_from_the_average():
 
 
 # --------------------------------------------------------------------------
+# Quantization constraint (J.3)
+# --------------------------------------------------------------------------
+
+def _qco_frame(s, W, H, qf):
+    Wb, Hb = (W + 7) // 8, (H + 7) // 8
+    return dict(strategy=np.full((Hb, Wb), s, np.uint8), qf=np.asarray(qf, np.uint8))
+
+
+def _corner(s):
+    bx, by = O.varblock_size(s)
+    return (bx // 8, by // 8) if s in DCT_FAMILY else (1, 1)
+
+
+def test_qco_zero_and_small_residuals_pass_unchanged():
+    # a residual whose coefficients all lie inside their intervals comes back
+    # unchanged (the forward transform, scaled, is the exact inverse of the
+    # inverse transform), also on a ragged frame edge
+    W, H = 77, 45
+    strat = _rng(1).choice([0, 1, 2, 3, 12, 13, 14], size=((H + 7) // 8, (W + 7) // 8))
+    strat = strat.astype(np.uint8)
+    strat[0:2, 0:2] = 4  # one DCT16 across the corner
+    strat[4:6, 8:10] = 4  # and one cut by the bottom edge
+    f = dict(strategy=strat, qf=_rng(2).integers(0, 256, size=strat.shape).astype(np.uint8))
+    p = O.params(W, H, qco=1)
+    orig = _rng(3).standard_normal((3, H, W))
+    np.testing.assert_array_equal(O.qco(p, f, orig, orig), orig)
+    filt = orig + 1e-9 * _rng(4).standard_normal(orig.shape)
+    np.testing.assert_allclose(O.qco(p, f, orig, filt), filt, rtol=0, atol=1e-13)
+
+
+@pytest.mark.parametrize("s", DCT_FAMILY + EIGHT_CLASS)
+def test_qco_hf_step_is_dequant_entry_times_acmul(s):
+    # one HF coefficient of amplitude A in the residual: kept below the step
+    # T = qco_interval_mul * DQ * AcMul, scaled down to T above it (so the
+    # whole residual is multiplied by T / A)
+    bx, by = O.varblock_size(s)
+    cx, cy = _corner(s)
+    qf = 37
+    p = O.params(bx, by, qco=1, global_scale=3, qco_interval_mul=0.75)
+    acmul = 65536.0 / (3 * (1 + qf))
+    f = _qco_frame(s, bx, by, np.full((by // 8, bx // 8), qf))
+    orig = _rng(s).standard_normal((3, by, bx))
+    for (ky, kx) in [(by - 1, bx - 1), (0, cx), (cy, 0)]:
+        resid = np.zeros((3, by, bx))
+        T = [0.75 * O.dequant_matrix(s, c)[ky, kx] * acmul for c in range(3)]
+        for c, a in enumerate((3.0, 0.5, -2.0)):
+            K = np.zeros((by, bx))
+            K[ky, kx] = a * T[c]
+            resid[c] = O.inverse_transform(s, K)
+        out = O.qco(p, f, orig, orig + resid)
+        for c, a in enumerate((3.0, 0.5, -2.0)):
+            want = resid[c] * (min(abs(a), 1.0) / abs(a))
+            scale = np.abs(resid[c]).max()
+            np.testing.assert_allclose(out[c] - orig[c], want, atol=1e-11 * scale, err_msg=str((s, ky, kx, c)))
+
+
+@pytest.mark.parametrize("s", DCT_FAMILY + EIGHT_CLASS)
+def test_qco_dc_samples_clamp_to_dc_step(s):
+    # a residual that is constant over each 8x8 block of the varblock's LF
+    # reconstruction: its DC samples (the block means) are clamped to
+    # +- qco_interval_mul * dc_mul / 2^extra_levels each, independently
+    bx, by = O.varblock_size(s)
+    cx, cy = _corner(s)
+    p = O.params(bx, by, qco=1, dc_mul=(0.5, 2.0, 0.125), extra_levels=(1, 0, 2))
+    step = [0.5 * 0.5 / 2, 0.5 * 2.0, 0.5 * 0.125 / 4]
+    f = _qco_frame(s, bx, by, np.zeros((by // 8, bx // 8)))
+    orig = _rng(s).standard_normal((3, by, bx))
+    D = _rng(50 + s).uniform(-2.0, 2.0, size=(3, cy, cx))
+    resid = np.zeros((3, by, bx))
+    for c in range(3):
+        K = np.zeros((by, bx))
+        K[:cy, :cx] = O.llf_from_dc(s, D[c]) if (cx, cy) != (1, 1) else D[c]
+        resid[c] = O.inverse_transform(s, K)
+    out = O.qco(p, f, orig, orig + resid)
+    for c in range(3):
+        d = out[c] - orig[c]
+        if (cx, cy) == (1, 1):
+            # 8x8 classes: the DC is the mean of the block
+            np.testing.assert_allclose(d.mean(), np.clip(D[c, 0, 0], -step[c], step[c]), atol=1e-12)
+        else:
+            means = d.reshape(cy, by // cy, cx, bx // cx).mean(axis=(1, 3))
+            np.testing.assert_allclose(means, np.clip(D[c], -step[c], step[c]), atol=1e-12)
+        # nothing but the LF part moves: the result is LF-only again
+        Kout = O.forward_transform(s, d)
+        Kout[:cy, :cx] = 0.0
+        assert np.abs(Kout).max() < 1e-9 * max(1.0, np.abs(d).max()) * bx * by
+
+
+def test_qco_is_a_projection():
+    # coefficients already inside their intervals are left alone: a second
+    # application changes nothing (frame of whole varblocks, so the cropped
+    # samples play no part)
+    W, H = 64, 64
+    strat = np.zeros((8, 8), np.uint8)
+    strat[0:4, 0:4] = 5
+    strat[4:6, 0:2] = 4
+    strat[4:5, 2:4] = 6
+    strat[4:6, 4:5] = 7
+    strat[6:8, 0:4] = 8
+    strat[4:8, 6:8] = 11
+    strat[0:4, 4:8] = np.array([[1, 2, 3, 12], [13, 14, 0, 1], [2, 3, 12, 13], [14, 0, 0, 3]])
+    f = dict(strategy=strat, qf=_rng(7).integers(0, 256, size=(8, 8)).astype(np.uint8))
+    p = O.params(W, H, qco=1)
+    orig = _rng(8).standard_normal((3, H, W))
+    filt = orig + 3.0 * _rng(9).standard_normal((3, H, W))
+    once = O.qco(p, f, orig, filt)
+    assert np.abs(once - filt).max() > 0.1  # the constraint is active
+    np.testing.assert_allclose(O.qco(p, f, orig, once), once, atol=1e-11)
+
+
+def test_qco_follows_the_filter_passes_in_decode():
+    W, H = 48, 40
+    Wb, Hb = 6, 5
+    rng = _rng(12)
+    f = _frame_of(0, W, H, rng.integers(-300, 300, size=(3, Hb, Wb)),
+                  ac=rng.integers(-6, 7, size=(3, 8 * Hb, 8 * Wb)).astype(np.int32), qf=9)
+    f["sharpness"] = rng.integers(0, 8, size=(Hb, Wb)).astype(np.uint8)
+    base = dict(dc_mul=(0.01, 0.01, 0.01), epf_iters=2)
+    pq = O.params(W, H, qco=1, **base)
+    st = O.decode_stages(pq, f)
+    want = O.qco(pq, f, st["recon"], st["epf"][-1][0])
+    np.testing.assert_array_equal(st["qco"], want)
+    np.testing.assert_allclose(O.decode(pq, f), st["rgb"], rtol=0, atol=1e-12)
+    # without filter passes there is nothing to constrain
+    p0q = O.params(W, H, qco=1, dc_mul=(0.01, 0.01, 0.01), epf_iters=0)
+    p0 = O.params(W, H, qco=0, dc_mul=(0.01, 0.01, 0.01), epf_iters=0)
+    np.testing.assert_array_equal(O.decode(p0q, f), O.decode(p0, f))
+    with pytest.raises(O.OracleError):
+        O.qco(O.params(W, H, qco=1, qco_interval_mul=-0.5), f, st["recon"], st["recon"])
+
+
+# --------------------------------------------------------------------------
 # Gaborish (J.4)
 # --------------------------------------------------------------------------
 
