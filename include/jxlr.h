@@ -109,6 +109,15 @@ typedef struct {
    * therefore requires: JXLR_E_PARAM otherwise).  Applied before the DC chroma
    * from luma and the LLF computation. */
   int32_t  dc_smoothing;
+  /* Quantization constraint of J.3 (loop_filter.qco, default 0), applied once
+   * after the last EPF pass (none without EPF): per varblock and channel the
+   * residual of the filter passes is transformed to coefficients, each
+   * clamped to +-qco_interval_mul quantization steps (dequantization weight
+   * times AcMul; for the LLF corner, its DC samples to +-qco_interval_mul *
+   * dc_mul[c], which again requires extra_levels 0), and transformed back.
+   * The batch functions reject it (JXLR_E_PARAM). */
+  int32_t  qco;
+  float    qco_interval_mul;  /* C.10 default 0.5; finite, >= 0 */
 } jxlr_frame_params;
 
 /* Input and output planes of one frame.  With Wb = ceil(xsize/8),
@@ -209,6 +218,15 @@ jxlr_status jxlr_epf_pass(jxlr_ctx* ctx, const jxlr_frame_params* p, const jxlr_
                           const uint8_t* info, const float* xyb_in, float* xyb_out,
                           size_t xyb_stride, uint8_t* guide_dbg, int32_t* sigma_dbg,
                           hipStream_t stream);
+
+/* Quantization constraint (J.3): xyb_orig holds the input of the first EPF
+ * pass, xyb_io the output of the last, which is constrained in place (the two
+ * buffers distinct, same stride).  Uses `info` and io->qf_minus_1; applies
+ * whether or not p->qco is set.  Pixels of ill-formed regions are left as
+ * they are. */
+jxlr_status jxlr_qco_pass(jxlr_ctx* ctx, const jxlr_frame_params* p, const jxlr_frame_io* io,
+                          const uint8_t* info, const float* xyb_orig, float* xyb_io,
+                          size_t xyb_stride, hipStream_t stream);
 
 /* Gaborish (J.4, when p->gab) and XYB -> RGB (L.2) into io->out in
  * p->out_format. */

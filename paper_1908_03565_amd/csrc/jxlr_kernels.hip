@@ -476,6 +476,85 @@ constexpr int kRecGroups = kRecTW / 4 * kRecTH;
 static_assert(offsetof(DeviceTables, dqs) % 16 == 0, "16-byte loads of dequantization weights");
 constexpr int kRecGPT = (kRecGroups + kRecThreads - 1) / kRecThreads;
 
+// I.2.4 on the coefficients of a tile in LDS, in place, in the phases below.
+// Regions with mma[r] >= 0 are left to the split-precision path.  192
+// threads; ends with a barrier.
+__device__ __attribute__((always_inline)) inline void inverse_passes(
+    float (*coef)[kRecTH][kRecLd], const uint8_t (*s_strat)[16], const uint8_t (*s_owner)[16],
+    const int* s_mma, const DeviceTables* __restrict__ T, int tid) {
+  const int wave = tid >> 6, lane = tid & 63;
+  // 8x8 transforms that are not separable products: DCT2, Identity and AFV,
+  // the 2x2 corner step of DCT4 and the DC pair of the two halves of DCT4x8
+  // and DCT8x4 (I.2.4.2-I.2.4.7).  Wave c: channel c.
+  if (lane < 32) {
+    const int c = wave, r = lane >> 4, lb = lane & 15;
+    const int s = s_strat[r][lb];
+    float* base = &coef[c][8 * (lb >> 2)][32 * r + 8 * (lb & 3)];
+    if (s == 12 || s == 13) {
+      // (0, 0) +- (0, 1) for DCT4x8 (halves stacked), (0, 0) +- (1, 0) for DCT8x4
+      const int o = s == 12 ? kRecLd : 1;
+      const float a0 = base[0], a1 = base[o];
+      base[0] = a0 + a1;
+      base[o] = a0 - a1;
+    } else if (s == 14) {
+      afv_inverse(base, kRecLd, T->afv);
+    } else if (s == 1 || s == 2 || s == 3) {
+      float* base = &coef[c][8 * (lb >> 2)][32 * r + 8 * (lb & 3)];
+      float v[64];
+#pragma unroll
+      for (int i = 0; i < 8; ++i)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) v[i * 8 + j] = base[i * kRecLd + j];
+      if (s == 2) {
+        aux_idct2x2<2>(v);
+        aux_idct2x2<4>(v);
+        aux_idct2x2<8>(v);
+      } else if (s == 1) {
+        identity_inverse(v);
+      } else {
+        aux_idct2x2<2>(v);
+      }
+#pragma unroll
+      for (int i = 0; i < 8; ++i)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) base[i * kRecLd + j] = v[i * 8 + j];
+    }
+  }
+  __syncthreads();
+
+  // Column and row passes: thread t works on region t / 96, channel
+  // (t mod 96) / 32 and column (row) t mod 32, so that two of the three waves
+  // see a single region (one transform type in the usual case) and only the
+  // middle one spans both.
+  // Column pass: the column's varblock segments one after the other.
+  {
+    const int r = tid / 96, c = (tid - 96 * r) >> 5, X = 32 * r + (tid & 31);
+    for (int br = 0; br < 4; ++br) {
+      const int lb = br * 4 + ((X & 31) >> 3);
+      const int s = s_strat[r][lb];
+      if (s == kAbsent || s == 1 || s == 2 || s == 14 || (s_owner[r][lb] >> 2) != br ||
+          s_mma[r] >= 0)
+        continue;
+      segment(&coef[c][8 * br][X], kRecLd, s == 3 || s == 12, 8 * vb_by(s));
+    }
+  }
+  __syncthreads();
+
+  // Row pass.
+  {
+    const int r = tid / 96, c = (tid - 96 * r) >> 5, Y = tid & 31;
+    for (int bc = 0; bc < 4; ++bc) {
+      const int lb = (Y >> 3) * 4 + bc;
+      const int s = s_strat[r][lb];
+      if (s == kAbsent || s == 1 || s == 2 || s == 14 || (s_owner[r][lb] & 3) != bc ||
+          s_mma[r] >= 0)
+        continue;
+      segment(&coef[c][Y][32 * r + 8 * bc], 1, s == 3 || s == 13, 8 * vb_bx(s));
+    }
+  }
+  __syncthreads();
+}
+
 // One 64x32 tile (tile column tbx, row tby) of the reconstruction.
 __device__ __attribute__((always_inline)) inline void recon_tile(const ReconArgs& a, int tbx, int tby) {
   __shared__ float coef[3][kRecTH][kRecLd];
@@ -665,76 +744,7 @@ __device__ __attribute__((always_inline)) inline void recon_tile(const ReconArgs
   }
   __syncthreads();
 
-  // 8x8 transforms that are not separable products: DCT2, Identity and AFV,
-  // the 2x2 corner step of DCT4 and the DC pair of the two halves of DCT4x8
-  // and DCT8x4 (I.2.4.2-I.2.4.7).  Wave c: channel c.
-  if (lane < 32) {
-    const int c = wave, r = lane >> 4, lb = lane & 15;
-    const int s = s_strat[r][lb];
-    float* base = &coef[c][8 * (lb >> 2)][32 * r + 8 * (lb & 3)];
-    if (s == 12 || s == 13) {
-      // (0, 0) +- (0, 1) for DCT4x8 (halves stacked), (0, 0) +- (1, 0) for DCT8x4
-      const int o = s == 12 ? kRecLd : 1;
-      const float a0 = base[0], a1 = base[o];
-      base[0] = a0 + a1;
-      base[o] = a0 - a1;
-    } else if (s == 14) {
-      afv_inverse(base, kRecLd, T->afv);
-    } else if (s == 1 || s == 2 || s == 3) {
-      float* base = &coef[c][8 * (lb >> 2)][32 * r + 8 * (lb & 3)];
-      float v[64];
-#pragma unroll
-      for (int i = 0; i < 8; ++i)
-#pragma unroll
-        for (int j = 0; j < 8; ++j) v[i * 8 + j] = base[i * kRecLd + j];
-      if (s == 2) {
-        aux_idct2x2<2>(v);
-        aux_idct2x2<4>(v);
-        aux_idct2x2<8>(v);
-      } else if (s == 1) {
-        identity_inverse(v);
-      } else {
-        aux_idct2x2<2>(v);
-      }
-#pragma unroll
-      for (int i = 0; i < 8; ++i)
-#pragma unroll
-        for (int j = 0; j < 8; ++j) base[i * kRecLd + j] = v[i * 8 + j];
-    }
-  }
-  __syncthreads();
-
-  // Column and row passes: thread t works on region t / 96, channel
-  // (t mod 96) / 32 and column (row) t mod 32, so that two of the three waves
-  // see a single region (one transform type in the usual case) and only the
-  // middle one spans both.
-  // Column pass: the column's varblock segments one after the other.
-  {
-    const int r = tid / 96, c = (tid - 96 * r) >> 5, X = 32 * r + (tid & 31);
-    for (int br = 0; br < 4; ++br) {
-      const int lb = br * 4 + ((X & 31) >> 3);
-      const int s = s_strat[r][lb];
-      if (s == kAbsent || s == 1 || s == 2 || s == 14 || (s_owner[r][lb] >> 2) != br ||
-          s_mma[r] >= 0)
-        continue;
-      segment(&coef[c][8 * br][X], kRecLd, s == 3 || s == 12, 8 * vb_by(s));
-    }
-  }
-  __syncthreads();
-
-  // Row pass.
-  {
-    const int r = tid / 96, c = (tid - 96 * r) >> 5, Y = tid & 31;
-    for (int bc = 0; bc < 4; ++bc) {
-      const int lb = (Y >> 3) * 4 + bc;
-      const int s = s_strat[r][lb];
-      if (s == kAbsent || s == 1 || s == 2 || s == 14 || (s_owner[r][lb] & 3) != bc ||
-          s_mma[r] >= 0)
-        continue;
-      segment(&coef[c][Y][32 * r + 8 * bc], 1, s == 3 || s == 13, 8 * vb_bx(s));
-    }
-  }
-  __syncthreads();
+  inverse_passes(coef, s_strat, s_owner, s_mma, T, tid);
 
   // Split-precision transform of the uniform regions (wave = channel).
   if (a.split) {
@@ -770,6 +780,397 @@ __device__ __attribute__((always_inline)) inline void recon_tile(const ReconArgs
         }
       }
     }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Quantization constraint (J.3).  The residual of the filters over each
+// varblock goes to the coefficient domain of the reconstruction (the exact
+// inverse of its I.2.4 phases, in the scaled domain the passes work in), each
+// coefficient is clamped to +-qco_interval_mul quantization steps (the LLF
+// corner through its DC samples), and the reconstruction's own inverse phases
+// bring it back.
+
+// Plain N-point DCT-II in registers, X_k = sum_n y_n cos(pi (2n + 1) k / (2N)),
+// the transpose of Dct3: the sums y_n + y_{N-1-n} form an N/2-point DCT-II
+// (the even outputs) and the differences meet the odd matrix transposed (the
+// odd outputs).
+template <int N>
+struct Dct2 {
+  template <typename Acc>
+  __device__ static inline void run(Acc&& x) {
+    constexpr int h = N / 2;
+    float u[h], w[h];
+#pragma unroll
+    for (int n = 0; n < h; ++n) {
+      u[n] = x(n) + x(N - 1 - n);
+      w[n] = x(n) - x(N - 1 - n);
+    }
+    Dct2<h>::run([&](int i) -> float& { return u[i]; });
+#pragma unroll
+    for (int m = 0; m < h; ++m) {
+      float acc = 0.0f;
+#pragma unroll
+      for (int n = 0; n < h; ++n) acc = fmaf(Dct3<N>::odd(n, m), w[n], acc);
+      x(2 * m + 1) = acc;
+    }
+#pragma unroll
+    for (int m = 0; m < h; ++m) x(2 * m) = u[m];
+  }
+};
+template <>
+struct Dct2<1> {
+  template <typename Acc>
+  __device__ static inline void run(Acc&&) {}
+};
+
+// Inverse of segment_dct<N>: x_k = (k ? 2 : 1) / N * DCT-II(y)_k (the scale
+// is a power of two, so exact).
+template <int N>
+__device__ inline void segment_fwd(float* v, int st) {
+  float r[N];
+#pragma unroll
+  for (int k = 0; k < N; ++k) r[k] = v[k * st];
+  Dct2<N>::run([&](int i) -> float& { return r[i]; });
+#pragma unroll
+  for (int k = 0; k < N; ++k) v[k * st] = r[k] * ((k ? 2.0f : 1.0f) / N);
+}
+
+// Inverse of segment_dct4: the first and second halves go back to the even
+// and the odd positions.
+__device__ inline void segment_fwd4(float* v, int st) {
+  float a[4], b[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    a[k] = v[k * st];
+    b[k] = v[(4 + k) * st];
+  }
+  Dct2<4>::run([&](int i) -> float& { return a[i]; });
+  Dct2<4>::run([&](int i) -> float& { return b[i]; });
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    v[(2 * k) * st] = a[k] * (k ? 0.5f : 0.25f);
+    v[(2 * k + 1) * st] = b[k] * (k ? 0.5f : 0.25f);
+  }
+}
+
+__device__ inline void segment_inv(float* v, int st, bool four, int n) {
+  if (four) segment_fwd4(v, st);
+  else if (n == 8) segment_fwd<8>(v, st);
+  else if (n == 16) segment_fwd<16>(v, st);
+  else segment_fwd<32>(v, st);
+}
+
+// Inverse of aux_idct2x2<S>: the S x S corner's interleaved 2x2 groups go
+// back to the four h x h quadrants (the 2x2 step is its own inverse up to 4).
+template <int S>
+__device__ inline void aux_dct2x2(float (&v)[64]) {
+  constexpr int h = S / 2;
+  float r[64];
+#pragma unroll
+  for (int i = 0; i < 64; ++i) r[i] = v[i];
+#pragma unroll
+  for (int y = 0; y < h; ++y)
+#pragma unroll
+    for (int x = 0; x < h; ++x) {
+      const float r00 = v[(2 * y) * 8 + 2 * x], r01 = v[(2 * y) * 8 + 2 * x + 1];
+      const float r10 = v[(2 * y + 1) * 8 + 2 * x], r11 = v[(2 * y + 1) * 8 + 2 * x + 1];
+      r[y * 8 + x] = 0.25f * ((r00 + r01) + (r10 + r11));
+      r[y * 8 + h + x] = 0.25f * ((r00 + r01) - (r10 + r11));
+      r[(h + y) * 8 + x] = 0.25f * ((r00 - r01) + (r10 - r11));
+      r[(h + y) * 8 + h + x] = 0.25f * ((r00 - r01) - (r10 - r11));
+    }
+#pragma unroll
+  for (int i = 0; i < 64; ++i) v[i] = r[i];
+}
+
+// Inverse of identity_inverse: per quarter, the sample at (1, 1) is s11, the
+// other interleaved coefficients are the samples minus s11 (the one at (1, 1)
+// from the sample at (0, 0)), and the quarter's DC is its sample mean; the
+// four DCs then go through the inverse 2x2 step.
+__device__ inline void identity_forward(float (&v)[64]) {
+  float k[64];
+#pragma unroll
+  for (int i = 0; i < 64; ++i) k[i] = 0.0f;
+#pragma unroll
+  for (int sy = 0; sy < 2; ++sy)
+#pragma unroll
+    for (int sx = 0; sx < 2; ++sx) {
+      float o[16];
+#pragma unroll
+      for (int iy = 0; iy < 4; ++iy)
+#pragma unroll
+        for (int ix = 0; ix < 4; ++ix) o[iy * 4 + ix] = v[(4 * sy + iy) * 8 + 4 * sx + ix];
+      const float s11 = o[1 * 4 + 1];
+      float sum = 0.0f;
+#pragma unroll
+      for (int i = 0; i < 16; ++i) sum += o[i];
+#pragma unroll
+      for (int iy = 0; iy < 4; ++iy)
+#pragma unroll
+        for (int ix = 0; ix < 4; ++ix) {
+          float c = o[iy * 4 + ix] - s11;
+          if (iy == 1 && ix == 1) c = o[0] - s11;
+          if (iy == 0 && ix == 0) c = sum / 16.0f;
+          k[(sy + 2 * iy) * 8 + sx + 2 * ix] = c;
+        }
+    }
+  aux_dct2x2<2>(k);
+#pragma unroll
+  for (int i = 0; i < 64; ++i) v[i] = k[i];
+}
+
+// Inverse of afv_inverse (the basis is orthonormal, so each quarter's
+// coefficients are its unmirrored samples times the basis), with the four
+// quarter DCs taken back through the Hadamard step to the 2x2 corner.
+__device__ inline void afv_forward(float* base, int ld, const float (*__restrict__ B)[16]) {
+  float smp[4][16];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int qx = q & 1, qy = q >> 1;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const int y = qy ? 3 - (i >> 2) : (i >> 2), x = qx ? 3 - (i & 3) : (i & 3);
+      smp[q][i] = base[(4 * qy + y) * ld + 4 * qx + x];
+    }
+  }
+  // every sample is in registers: coefficient j of each quarter is written
+  // as soon as it is summed
+  float d[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    float acc = 0.0f;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) acc = fmaf(B[0][i], smp[q][i], acc);
+    d[q] = acc;
+  }
+#pragma unroll 1
+  for (int j = 1; j < 16; ++j) {
+    const int ix = j & 3, iy = j >> 2;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      float acc = 0.0f;
+#pragma unroll
+      for (int i = 0; i < 16; ++i) acc = fmaf(B[j][i], smp[q][i], acc);
+      base[((q >> 1) + 2 * iy) * ld + (q & 1) + 2 * ix] = acc;
+    }
+  }
+  base[0] = ((d[0] + d[1]) + (d[2] + d[3])) * (1.0f / 16.0f);
+  base[1] = ((d[0] + d[1]) - (d[2] + d[3])) * (1.0f / 16.0f);
+  base[ld] = ((d[0] - d[1]) + (d[2] - d[3])) * (1.0f / 16.0f);
+  base[ld + 1] = ((d[0] - d[1]) - (d[2] - d[3])) * (1.0f / 16.0f);
+}
+
+struct QcoArgs {
+  int W, H, Wb, Hb;
+  const uint8_t* info;
+  const uint8_t* qf;
+  size_t map_stride;
+  const float* orig;  // input of the first filter pass
+  float* io;          // output of the last pass; constrained in place
+  size_t stride;
+  float gscale;       // global_scale (exact)
+  float mul;          // qco_interval_mul
+  float dc_step[3];   // qco_interval_mul * DC multiplier
+  const DeviceTables* __restrict__ tab;
+};
+
+// One 64x32 tile: every varblock lies inside one of its two 32x32 regions.
+__device__ __attribute__((always_inline)) inline void qco_tile(const QcoArgs& a, int tbx, int tby) {
+  __shared__ float coef[3][kRecTH][kRecLd];
+  __shared__ float s_acmul[32];
+  __shared__ uint8_t s_owner[2][16], s_strat[2][16];
+  __shared__ int s_bad[2];
+  __shared__ int s_mma[2];
+
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63;
+  const int x0 = kRecTW * tbx, y0 = kRecTH * tby;
+  const int gbx0 = x0 / 8, gby0 = y0 / 8;
+  const DeviceTables* __restrict__ T = a.tab;
+  const size_t plane = size_t(a.H) * a.stride;
+
+  if (tid < 2) {
+    s_bad[tid] = 0;
+    s_mma[tid] = -1;
+  }
+  __syncthreads();
+  if (tid < 32) {
+    load_tile_info(a.info, a.Wb, a.Hb, gbx0, gby0, tid, s_strat, s_owner, s_bad);
+    const int bx = gbx0 + (tid & 7), by = gby0 + (tid >> 3);
+    const bool in = bx < a.Wb && by < a.Hb;
+    const float qfv = float(1 + a.qf[in ? size_t(by) * a.map_stride + bx : 0]);
+    s_acmul[tid] = 65536.0f / (a.gscale * qfv);
+  }
+  // the residual of the filters; samples outside the frame were never
+  // filtered and count as 0
+  for (int i = tid; i < 3 * kRecTH * kRecTW; i += kRecThreads) {
+    const int c = i / (kRecTH * kRecTW), rem = i - c * (kRecTH * kRecTW);
+    const int Y = rem / kRecTW, X = rem - Y * kRecTW;
+    const int gx = x0 + X, gy = y0 + Y;
+    float d = 0.0f;
+    if (gx < a.W && gy < a.H) {
+      const size_t o = c * plane + size_t(gy) * a.stride + gx;
+      d = a.io[o] - a.orig[o];
+    }
+    coef[c][Y][X] = d;
+  }
+  __syncthreads();
+  if (tid < 2 && s_bad[tid])
+    for (int i = 0; i < 16; ++i) s_strat[tid][i] = kAbsent;
+  __syncthreads();
+
+  // Row passes, then column passes, of the forward transform (the inverse
+  // phases in reverse order; thread mapping as in inverse_passes).
+  {
+    const int r = tid / 96, c = (tid - 96 * r) >> 5, Y = tid & 31;
+    for (int bc = 0; bc < 4; ++bc) {
+      const int lb = (Y >> 3) * 4 + bc;
+      const int s = s_strat[r][lb];
+      if (s == kAbsent || s == 1 || s == 2 || s == 14 || (s_owner[r][lb] & 3) != bc) continue;
+      segment_inv(&coef[c][Y][32 * r + 8 * bc], 1, s == 3 || s == 13, 8 * vb_bx(s));
+    }
+  }
+  __syncthreads();
+  {
+    const int r = tid / 96, c = (tid - 96 * r) >> 5, X = 32 * r + (tid & 31);
+    for (int br = 0; br < 4; ++br) {
+      const int lb = br * 4 + ((X & 31) >> 3);
+      const int s = s_strat[r][lb];
+      if (s == kAbsent || s == 1 || s == 2 || s == 14 || (s_owner[r][lb] >> 2) != br) continue;
+      segment_inv(&coef[c][8 * br][X], kRecLd, s == 3 || s == 12, 8 * vb_by(s));
+    }
+  }
+  __syncthreads();
+  if (lane < 32) {
+    const int c = wave, r = lane >> 4, lb = lane & 15;
+    const int s = s_strat[r][lb];
+    float* base = &coef[c][8 * (lb >> 2)][32 * r + 8 * (lb & 3)];
+    if (s == 12 || s == 13) {
+      const int o = s == 12 ? kRecLd : 1;
+      const float b0 = base[0], b1 = base[o];
+      base[0] = 0.5f * (b0 + b1);
+      base[o] = 0.5f * (b0 - b1);
+    } else if (s == 14) {
+      afv_forward(base, kRecLd, T->afv);
+    } else if (s == 1 || s == 2 || s == 3) {
+      float v[64];
+#pragma unroll
+      for (int i = 0; i < 8; ++i)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) v[i * 8 + j] = base[i * kRecLd + j];
+      if (s == 2) {
+        aux_dct2x2<8>(v);
+        aux_dct2x2<4>(v);
+        aux_dct2x2<2>(v);
+      } else if (s == 1) {
+        identity_forward(v);
+      } else {
+        aux_dct2x2<2>(v);
+      }
+#pragma unroll
+      for (int i = 0; i < 8; ++i)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) base[i * kRecLd + j] = v[i * 8 + j];
+    }
+  }
+  __syncthreads();
+
+  // Clamp.  Outside the LLF corner: +-mul AcMul dqs (the quantization step
+  // in the scaled domain).  The corner of each varblock (one thread per
+  // varblock and channel): its DC samples from the scaled LLF (b = a^-1 per
+  // axis), clamped to +-mul dc_mul, and back (a per axis).
+  for (int i = tid; i < 3 * kRecTH * kRecTW; i += kRecThreads) {
+    const int c = i / (kRecTH * kRecTW), rem = i - c * (kRecTH * kRecTW);
+    const int Y = rem / kRecTW, X = rem - Y * kRecTW, r = X >> 5;
+    const int lb = (Y >> 3) * 4 + ((X & 31) >> 3);
+    const int s = s_strat[r][lb];
+    if (s == kAbsent) continue;
+    const int o = s_owner[r][lb];
+    const int x = (X & 31) - 8 * (o & 3), y = Y - 8 * (o >> 2);
+    const int cx = vb_bx(s), cy = vb_by(s);
+    if (x < cx && y < cy) continue;
+    const int sz = 64 * cx * cy;
+    const float t = a.mul * s_acmul[(o >> 2) * 8 + 4 * r + (o & 3)] *
+                    T->dqs[dq_off_lut(s) + c * sz + y * 8 * cx + x];
+    coef[c][Y][X] = fminf(fmaxf(coef[c][Y][X], -t), t);
+  }
+  if (tid < 96) {
+    const int c = tid >> 5, b = tid & 31;
+    const int bxl = b & 7, byl = b >> 3, r = bxl >> 2, lb = byl * 4 + (bxl & 3);
+    const int s = s_strat[r][lb];
+    if (s != kAbsent && s_owner[r][lb] == lb) {
+      const int cx = vb_bx(s), cy = vb_by(s);
+      // per-axis maps zero-padded to 4x4 (a 1-sample axis is the identity)
+      auto axis = [&](int n, const float* m2, const float* m4, float (&m)[4][4]) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            m[i][j] = n == 4 ? m4[i * 4 + j]
+                     : n == 2 ? (i < 2 && j < 2 ? m2[i * 2 + j] : 0.0f)
+                              : (i == 0 && j == 0 ? 1.0f : 0.0f);
+      };
+      float bx_[4][4], by_[4][4], L[4][4], D[4][4];
+      axis(cx, T->b16s, T->b32s, bx_);
+      axis(cy, T->b16s, T->b32s, by_);
+#pragma unroll
+      for (int y = 0; y < 4; ++y)
+#pragma unroll
+        for (int x = 0; x < 4; ++x) L[y][x] = (y < cy && x < cx) ? coef[c][8 * byl + y][8 * bxl + x] : 0.0f;
+      // D = By L Bx^T, clamped
+#pragma unroll
+      for (int y = 0; y < 4; ++y)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          float acc = 0.0f;
+#pragma unroll
+          for (int x = 0; x < 4; ++x) acc = fmaf(bx_[i][x], L[y][x], acc);
+          D[y][i] = acc;
+        }
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          float acc = 0.0f;
+#pragma unroll
+          for (int y = 0; y < 4; ++y) acc = fmaf(by_[j][y], D[y][i], acc);
+          L[j][i] = fminf(fmaxf(acc, -a.dc_step[c]), a.dc_step[c]);
+        }
+      // back: Ay D' Ax^T
+      axis(cx, T->a16s, T->a32s, bx_);
+      axis(cy, T->a16s, T->a32s, by_);
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int x = 0; x < 4; ++x) {
+          float acc = 0.0f;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) acc = fmaf(bx_[x][i], L[j][i], acc);
+          D[j][x] = acc;
+        }
+#pragma unroll
+      for (int y = 0; y < 4; ++y)
+#pragma unroll
+        for (int x = 0; x < 4; ++x) {
+          float acc = 0.0f;
+#pragma unroll
+          for (int j = 0; j < 4; ++j) acc = fmaf(by_[y][j], D[j][x], acc);
+          if (y < cy && x < cx) coef[c][8 * byl + y][8 * bxl + x] = acc;
+        }
+    }
+  }
+  __syncthreads();
+
+  inverse_passes(coef, s_strat, s_owner, s_mma, T, tid);
+
+  for (int i = tid; i < 3 * kRecTH * kRecTW; i += kRecThreads) {
+    const int c = i / (kRecTH * kRecTW), rem = i - c * (kRecTH * kRecTW);
+    const int Y = rem / kRecTW, X = rem - Y * kRecTW;
+    const int gx = x0 + X, gy = y0 + Y;
+    if (gx >= a.W || gy >= a.H || s_bad[X >> 5]) continue;
+    const size_t o = c * plane + size_t(gy) * a.stride + gx;
+    a.io[o] = a.orig[o] + coef[c][Y][X];
   }
 }
 
@@ -1325,6 +1726,10 @@ __global__ __launch_bounds__(kRecThreads, kRecMinBlocks) void recon_kernel(Recon
   const int t = xcd_tile(blockIdx.x, gridDim.x);
   recon_tile(a, t % tiles_x, t / tiles_x);
 }
+__global__ __launch_bounds__(kRecThreads) void qco_kernel(QcoArgs a, int tiles_x) {
+  const int t = xcd_tile(blockIdx.x, gridDim.x);
+  qco_tile(a, t % tiles_x, t / tiles_x);
+}
 __global__ __launch_bounds__(kEpfThreads, kEpfMinBlocks) void epf_kernel(EpfArgs a, int tiles_x) {
   const int t = xcd_tile(blockIdx.x, gridDim.x);
   epf_tile(a, t % tiles_x, t / tiles_x);
@@ -1495,8 +1900,10 @@ jxlr_status check_params(const jxlr_frame_params* p) {
   if (p->out_format < JXLR_OUT_F32 || p->out_format > JXLR_OUT_U16_SRGB) return JXLR_E_PARAM;
   if (p->idct_split < 0 || p->idct_split > 1) return JXLR_E_PARAM;
   if (p->dc_smoothing < 0 || p->dc_smoothing > 1) return JXLR_E_PARAM;
-  if (p->dc_smoothing &&
-      (p->extra_levels[0] != 0 || p->extra_levels[1] != 0 || p->extra_levels[2] != 0))
+  const bool el0 = p->extra_levels[0] == 0 && p->extra_levels[1] == 0 && p->extra_levels[2] == 0;
+  if (p->dc_smoothing && !el0) return JXLR_E_PARAM;
+  if (p->qco < 0 || p->qco > 1) return JXLR_E_PARAM;
+  if (p->qco && (!el0 || !(p->qco_interval_mul >= 0.0f) || !std::isfinite(p->qco_interval_mul)))
     return JXLR_E_PARAM;
   return JXLR_OK;
 }
@@ -1559,6 +1966,8 @@ jxlr_status jxlr_params_default(jxlr_frame_params* p, uint32_t xsize, uint32_t y
   p->epf_quant_mul = 20.0f;
   p->epf_sigma_max = 170;
   p->epf_sigma_shift = 0;
+  p->qco = 0;
+  p->qco_interval_mul = 0.5f;
   const float m[9] = {2542.56835937500000f, -2326.53173828125000f, 44.17734527587891f,
                       -698.04852294921875f, 1012.71777343750000f,  -76.22974395751953f,
                       -827.36480712890625f, 709.83502197265625f,   451.38488769531250f};
@@ -1631,6 +2040,8 @@ jxlr_status jxlr_validate_maps_host(const jxlr_frame_params* p, const uint8_t* s
   return JXLR_OK;
 }
 
+}  // extern "C"
+
 namespace {
 size_t round256(size_t v) { return (v + 255) & ~size_t(255); }
 size_t info_bytes(const jxlr_frame_params* p) {
@@ -1639,11 +2050,20 @@ size_t info_bytes(const jxlr_frame_params* p) {
 size_t xyb_bytes(const jxlr_frame_params* p) {
   return round256(size_t(3) * p->xsize * p->ysize * sizeof(float));
 }
+// XYB buffers of a decode: the reconstruction, and the EPF passes' outputs
+// alternating over one more buffer, or two more when the quantization
+// constraint needs the reconstruction kept past a second pass.
+int xyb_buffers(const jxlr_frame_params* p) {
+  if (p->epf_iters == 0) return 1;
+  return p->qco && p->epf_iters > 1 ? 3 : 2;
+}
 }  // namespace
+
+extern "C" {
 
 size_t jxlr_workspace_bytes(const jxlr_frame_params* p) {
   if (check_params(p) != JXLR_OK) return 0;
-  return info_bytes(p) + (p->epf_iters > 0 ? 2 : 1) * xyb_bytes(p);
+  return info_bytes(p) + xyb_buffers(p) * xyb_bytes(p);
 }
 
 }  // extern "C"
@@ -1849,6 +2269,42 @@ jxlr_status jxlr_epf_pass(jxlr_ctx* ctx, const jxlr_frame_params* p, const jxlr_
   return launch_status(hipGetLastError());
 }
 
+jxlr_status jxlr_qco_pass(jxlr_ctx* ctx, const jxlr_frame_params* p, const jxlr_frame_io* io,
+                          const uint8_t* info, const float* orig, float* xyb_io, size_t stride,
+                          hipStream_t stream) {
+  if (!ctx || !info || !orig || !xyb_io) return JXLR_E_NULL;
+  jxlr_status st = check_params(p);
+  if (st) return st;
+  if ((st = check_maps_io(p, io, false))) return st;
+  if (stride < p->xsize) return JXLR_E_SIZE;
+  if (orig == xyb_io) return JXLR_E_PARAM;
+  // the constraint itself is applied here whatever p->qco says; its step
+  // needs the DcQuantField of extra_levels 0 and a usable multiplier
+  if (p->extra_levels[0] || p->extra_levels[1] || p->extra_levels[2] ||
+      !(p->qco_interval_mul >= 0.0f) || !std::isfinite(p->qco_interval_mul))
+    return JXLR_E_PARAM;
+  QcoArgs a{};
+  a.W = int(p->xsize);
+  a.H = int(p->ysize);
+  a.Wb = blocks_of(p->xsize);
+  a.Hb = blocks_of(p->ysize);
+  a.info = info;
+  a.qf = io->qf_minus_1;
+  a.map_stride = io->map_stride;
+  a.orig = orig;
+  a.io = xyb_io;
+  a.stride = stride;
+  a.gscale = float(p->global_scale);
+  a.mul = p->qco_interval_mul;
+  for (int c = 0; c < 3; ++c) a.dc_step[c] = p->qco_interval_mul * p->dc_mul[c];
+  a.tab = ctx->tables;
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return JXLR_E_HIP;
+  hipLaunchKernelGGL(qco_kernel, dim3(tiles_x(p) * tiles_y(p)), dim3(kRecThreads), 0, stream, a,
+                     tiles_x(p));
+  return launch_status(hipGetLastError());
+}
+
 jxlr_status jxlr_finish(jxlr_ctx* ctx, const jxlr_frame_params* p, const jxlr_frame_io* io,
                         const float* xyb, size_t stride, hipStream_t stream) {
   if (!xyb) return JXLR_E_NULL;
@@ -1872,17 +2328,24 @@ jxlr_status jxlr_decode(jxlr_ctx* ctx, const jxlr_frame_params* p, const jxlr_fr
   if (ws_bytes < need) return JXLR_E_WORKSPACE;
   char* base = static_cast<char*>(ws);
   uint8_t* info = reinterpret_cast<uint8_t*>(base);
-  float* bufa = reinterpret_cast<float*>(base + info_bytes(p));
-  float* bufb = reinterpret_cast<float*>(base + info_bytes(p) + xyb_bytes(p));
+  float* buf[3];
+  for (int i = 0; i < 3; ++i)
+    buf[i] = reinterpret_cast<float*>(base + info_bytes(p) + size_t(i) * xyb_bytes(p));
   const size_t stride = p->xsize;
   if ((st = jxlr_block_info(ctx, p, io, info, stream))) return st;
-  if ((st = jxlr_reconstruct(ctx, p, io, info, bufa, stride, stream))) return st;
+  if ((st = jxlr_reconstruct(ctx, p, io, info, buf[0], stride, stream))) return st;
+  // the passes alternate between two buffers; with the quantization
+  // constraint the reconstruction in buf[0] stays untouched
+  const bool qco = p->qco && p->epf_iters > 0;
+  float* cur = buf[0];
   for (int it = 0; it < p->epf_iters; ++it) {
-    if ((st = jxlr_epf_pass(ctx, p, io, info, bufa, bufb, stride, nullptr, nullptr, stream)))
+    float* dst = (it & 1) ? (qco ? buf[2] : buf[0]) : buf[1];
+    if ((st = jxlr_epf_pass(ctx, p, io, info, cur, dst, stride, nullptr, nullptr, stream)))
       return st;
-    std::swap(bufa, bufb);
+    cur = dst;
   }
-  return jxlr_finish(ctx, p, io, bufa, stride, stream);
+  if (qco && (st = jxlr_qco_pass(ctx, p, io, info, buf[0], cur, stride, stream))) return st;
+  return jxlr_finish(ctx, p, io, cur, stride, stream);
 }
 
 }  // extern "C"
@@ -1976,7 +2439,7 @@ extern "C" {
 size_t jxlr_batch_workspace_bytes(int n, const jxlr_frame_params* p) {
   if (n <= 0 || !p) return 0;
   for (int i = 0; i < n; ++i)
-    if (check_params(&p[i]) != JXLR_OK) return 0;
+    if (check_params(&p[i]) != JXLR_OK || p[i].qco) return 0;
   return batch_layout(n, p).total;
 }
 
@@ -1988,6 +2451,7 @@ jxlr_status jxlr_batch_prepare(jxlr_ctx* ctx, int n, const jxlr_frame_params* p,
   for (int i = 0; i < n; ++i) {
     jxlr_status st = check_params(&p[i]);
     if (st) return st;
+    if (p[i].qco) return JXLR_E_PARAM;  // the batch stages have no constraint pass
   }
   const BatchLayout L = batch_layout(n, p);
   if (ws_bytes < L.total) return JXLR_E_WORKSPACE;

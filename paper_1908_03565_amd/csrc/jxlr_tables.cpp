@@ -469,6 +469,33 @@ bool build_tables(DeviceTables* t) {
         as[x * n + i] = float(v * transform_scale(8 * n, x));
       }
   }
+  // b = a^-1 for the scaled LLF-from-DC axis maps (Gauss-Jordan, partial
+  // pivoting, in double from the double-precision entries).
+  for (int n : {2, 4}) {
+    double a[4][8] = {};
+    for (int x = 0; x < n; ++x) {
+      for (int i = 0; i < n; ++i)
+        a[x][i] = scale_i(n, x) * ortho(n, i, x) * scale_f(n, 8 * n, x) * transform_scale(8 * n, x);
+      a[x][n + x] = 1.0;
+    }
+    for (int col = 0; col < n; ++col) {
+      int piv = col;
+      for (int r = col + 1; r < n; ++r)
+        if (std::fabs(a[r][col]) > std::fabs(a[piv][col])) piv = r;
+      if (!(std::fabs(a[piv][col]) > 0.0)) return false;
+      for (int j = 0; j < 2 * n; ++j) std::swap(a[col][j], a[piv][j]);
+      const double d = a[col][col];
+      for (int j = 0; j < 2 * n; ++j) a[col][j] /= d;
+      for (int r = 0; r < n; ++r)
+        if (r != col) {
+          const double f = a[r][col];
+          for (int j = 0; j < 2 * n; ++j) a[r][j] -= f * a[col][j];
+        }
+    }
+    float* b = n == 2 ? t->b16s : t->b32s;
+    for (int i = 0; i < n; ++i)
+      for (int x = 0; x < n; ++x) b[i * n + x] = float(a[i][n + x]);
+  }
   build_mfma_operands(t);
   for (int j = 0; j < 16; ++j)
     for (int i = 0; i < 16; ++i) t->afv[j][i] = float(kAfvBasis[j][i]);

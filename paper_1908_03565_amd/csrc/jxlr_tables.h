@@ -82,6 +82,10 @@ struct DeviceTables {
   alignas(16) uint16_t mfma_a[3][2][2][64][8];
   // AFV basis (I.2.2): afv[j][i] = basis vector j at 4x4 index i.
   float afv[16][16];
+  // Inverses of a16s and a32s: DC samples from the scaled LLF, one axis
+  // (quantization constraint, J.3).
+  float b16s[2 * 2];
+  float b32s[4 * 4];
 };
 
 // Fills t on the host.  Returns false if a dequantization matrix entry is not

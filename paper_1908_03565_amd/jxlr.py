@@ -41,6 +41,8 @@ class FrameParams(C.Structure):
         ("out_format", C.c_int32),
         ("idct_split", C.c_int32),
         ("dc_smoothing", C.c_int32),
+        ("qco", C.c_int32),
+        ("qco_interval_mul", C.c_float),
     ]
 
 
@@ -105,6 +107,8 @@ _SIGS = {
     "jxlr_epf_pass": ([C.c_void_p, C.POINTER(FrameParams), C.POINTER(FrameIO), C.c_void_p,
                        C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p, C.c_void_p],
                       C.c_int),
+    "jxlr_qco_pass": ([C.c_void_p, C.POINTER(FrameParams), C.POINTER(FrameIO), C.c_void_p,
+                       C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p], C.c_int),
     "jxlr_finish": ([C.c_void_p, C.POINTER(FrameParams), C.POINTER(FrameIO), C.c_void_p,
                      C.c_size_t, C.c_void_p], C.c_int),
     "jxlr_batch_workspace_bytes": ([C.c_int, C.POINTER(FrameParams)], C.c_size_t),
@@ -310,6 +314,11 @@ class Context:
     def finish(self, p, df, xyb, out, stream=None):
         _check(lib().jxlr_finish(self.handle, C.byref(p), C.byref(df.io(out)), xyb.data_ptr(),
                                  xyb.shape[2], _stream_handle(stream)), "finish")
+
+    def qco_pass(self, p, df, info, xyb_orig, xyb_io, stream=None):
+        _check(lib().jxlr_qco_pass(self.handle, C.byref(p), C.byref(df.io()), info.data_ptr(),
+                                   xyb_orig.data_ptr(), xyb_io.data_ptr(), xyb_io.shape[2],
+                                   _stream_handle(stream)), "qco_pass")
 
     def decode(self, p, df, out, ws, stream=None, io=None):
         io = df.io(out) if io is None else io

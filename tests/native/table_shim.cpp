@@ -30,4 +30,6 @@ const uint8_t* shim_start8() { return g_tables.srgb_start8; }
 int shim_bucket0() { return jxlr::kSrgbBucket0; }
 int shim_buckets() { return jxlr::kSrgbBuckets; }
 const float* shim_afv() { return &g_tables.afv[0][0]; }
+const float* shim_b16s() { return g_tables.b16s; }
+const float* shim_b32s() { return g_tables.b32s; }
 }

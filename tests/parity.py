@@ -77,6 +77,9 @@ def gpu_stages(ctx, p, df):
         ctx.epf_pass(p, df, info, cur, nxt, guide, sigma)
         res["epf"].append((nxt.cpu().numpy(), guide.cpu().numpy(), sigma.cpu().numpy()))
         cur = nxt
+    if p.qco and p.epf_iters > 0:
+        ctx.qco_pass(p, df, info, xyb, cur)
+        res["qco"] = cur.cpu().numpy()
     out = ctx.empty_out(p)
     ctx.finish(p, df, cur, out)
     res["out"] = out.cpu().numpy()
@@ -84,11 +87,44 @@ def gpu_stages(ctx, p, df):
     return res
 
 
-def compare_rgb(p, gpu, orc):
+def varblock_ids(strategy):
+    """Varblock index of every block of a DctSelect map (raster order of the
+    top-left blocks, each varblock cx x cy blocks of its type)."""
+    from oracle import oracle as O
+    Hb, Wb = strategy.shape
+    ids = -np.ones((Hb, Wb), np.int64)
+    n = 0
+    for by in range(Hb):
+        for bx in range(Wb):
+            if ids[by, bx] >= 0:
+                continue
+            bw, bh = O.varblock_size(int(strategy[by, bx]))
+            ids[by:by + bh // 8, bx:bx + bw // 8] = n
+            n += 1
+    return ids
+
+
+def spread_to_varblocks(mask, strategy):
+    """Every pixel of a varblock that holds a masked pixel (the quantization
+    constraint mixes the samples of a varblock)."""
+    H, W = mask.shape
+    ids = varblock_ids(strategy)
+    Hb, Wb = ids.shape
+    pad = np.zeros((8 * Hb, 8 * Wb), bool)
+    pad[:H, :W] = mask
+    hit_blocks = pad.reshape(Hb, 8, Wb, 8).any(axis=(1, 3))
+    hit = np.isin(ids, np.unique(ids[hit_blocks]))
+    return np.kron(hit, np.ones((8, 8), bool))[:H, :W]
+
+
+def compare_rgb(p, gpu, orc, strategy=None):
     """Max-abs error of the final [0,1]-scaled RGB outside flip-affected
-    pixels, plus the flip statistics."""
+    pixels, plus the flip statistics.  With the quantization constraint on,
+    pass the DctSelect map: the mask spreads over whole varblocks."""
     mask, stats = affected_mask(p, [(g, s) for _, g, s in gpu["epf"]],
                                 [(g, s) for _, g, s in orc["epf"]])
+    if p.qco and p.epf_iters > 0:
+        mask = spread_to_varblocks(mask, strategy)
     if p.gab:
         mask = dilate(mask, range(-1, 2), range(-1, 2))
     err = np.abs(gpu["out"].astype(np.float64) - orc["rgb"])

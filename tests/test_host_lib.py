@@ -90,6 +90,17 @@ def test_parameter_ranges():
     p = J.params(64, 64, dc_smoothing=1, extra_levels=(0, 1, 0))
     assert J.validate_maps_host(p, f) == 7
     assert J.validate_maps_host(J.params(64, 64, dc_smoothing=1), f) == 0
+    # the quantization constraint: a flag, a finite non-negative multiplier,
+    # and the DC step from the multipliers (extra_levels 0)
+    for kw in (dict(qco=2), dict(qco=-1), dict(qco=1, qco_interval_mul=-0.25),
+               dict(qco=1, qco_interval_mul=float("nan")), dict(qco=1, qco_interval_mul=float("inf")),
+               dict(qco=1, extra_levels=(1, 0, 0))):
+        p = J.params(64, 64, **kw)
+        assert J.validate_maps_host(p, f) == 7, kw
+        assert J.workspace_bytes(p) == 0, kw
+    assert J.validate_maps_host(J.params(64, 64, qco=1, qco_interval_mul=0.0), f) == 0
+    d = J.params(64, 64)
+    assert d.qco == 0 and d.qco_interval_mul == 0.5  # C.10 defaults
 
 
 def test_workspace_bytes():
@@ -100,6 +111,12 @@ def test_workspace_bytes():
     p2 = J.params(100, 50, epf_iters=2)
     assert J.workspace_bytes(p2) - one >= 3 * 100 * 50 * 4
     assert J.workspace_bytes(p2) % 256 == 0
+    # the quantization constraint keeps the reconstruction past a second
+    # pass: one more plane set then, none with a single pass
+    xyb = J.workspace_bytes(p2) - one
+    assert J.workspace_bytes(J.params(100, 50, epf_iters=2, qco=1)) == J.workspace_bytes(p2) + xyb
+    assert J.workspace_bytes(J.params(100, 50, epf_iters=1, qco=1)) == J.workspace_bytes(p2)
+    assert J.workspace_bytes(J.params(100, 50, epf_iters=0, qco=1)) == one
 
 
 def test_batch_workspace_bytes():
@@ -112,6 +129,8 @@ def test_batch_workspace_bytes():
     assert J.batch_workspace_bytes(ps[:1]) > J.workspace_bytes(ps[0])
     assert J.batch_workspace_bytes([]) == 0
     assert J.batch_workspace_bytes(ps + [J.params(64, 64, epf_iters=4)]) == 0
+    # the batch stages have no constraint pass
+    assert J.batch_workspace_bytes(ps + [J.params(64, 64, qco=1)]) == 0
 
 
 # --- the library's constant tables versus the oracle's --------------------
@@ -125,7 +144,7 @@ def shim(tmp_path_factory):
                     os.path.join(csrc, "jxlr_tables.cpp"), "-o", str(out)], check=True)
     L = C.CDLL(str(out))
     for f in ("shim_t8", "shim_t16", "shim_t32", "shim_m4", "shim_a16", "shim_a32", "shim_dq",
-              "shim_dqs", "shim_a16s", "shim_a32s"):
+              "shim_dqs", "shim_a16s", "shim_a32s", "shim_b16s", "shim_b32s"):
         getattr(L, f).restype = C.POINTER(C.c_float)
     L.shim_mul.restype = C.POINTER(C.c_int32)
     L.shim_thr.restype = C.POINTER(C.c_float)
@@ -228,6 +247,18 @@ def test_prescaled_tables_match_oracle(shim):
         ref = np.stack([O.llf_from_dc(s, e.reshape(1, n)).ravel() for e in np.eye(n)], axis=1)
         ref = ref * _col_scale(8 * n)[:n, None]
         np.testing.assert_allclose(a, ref, atol=2e-7)
+
+
+def test_dc_from_llf_tables_match_oracle(shim):
+    # b16s / b32s take the scaled LLF of one axis back to DC samples: the
+    # oracle's I.2.6 on DCT16x8 / DCT32x8 with the scale removed again
+    for s, n, f, fa in ((6, 2, shim.shim_b16s, shim.shim_a16s), (8, 4, shim.shim_b32s, shim.shim_a32s)):
+        b = _arr(f(), n * n).reshape(n, n)
+        a = _arr(fa(), n * n).reshape(n, n)
+        np.testing.assert_allclose(b @ a, np.eye(n), atol=1e-6)
+        sc = _col_scale(8 * n)[:n]
+        ref = np.stack([O.dc_from_llf(s, (e / sc).reshape(1, n)).ravel() for e in np.eye(n)], axis=1)
+        np.testing.assert_allclose(b, ref, atol=2e-6)
 
 
 def test_schedule_cache_roundtrip(tmp_path):
