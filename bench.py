@@ -48,6 +48,9 @@ EPF_OPS_PER_PX = 56 * (1 + 5 + 7 + 4)
 # out for reconstruct; f32 XYB in, f32 / u8 / u16 RGB out for finish.
 RECON_BYTES_PER_PX = 12 + 12
 FINISH_BYTES_PER_PX = {0: 12 + 12, 1: 12 + 3, 2: 12 + 6}
+# quantization constraint: f32 XYB before and after the filter in, the
+# constrained f32 XYB out
+QCO_BYTES_PER_PX = 12 + 12 + 12
 
 METRIC = "decoded MP/s (coeffs->RGB) at stated max-abs err vs FP64; p50/p99 latency"
 
@@ -130,33 +133,41 @@ def bench_frame(args, J, wl, torch, np):
     log(f"bench: generating workload {args.workload}")
     frame = getattr(wl, args.workload)()
     W, H = frame["xsize"], frame["ysize"]
-    p = J.params(W, H, out_format=frame["out_format"], idct_split=int(args.split), **frame["params"])
+    qco = int(args.qco and frame["params"]["epf_iters"] > 0)
+    p = J.params(W, H, out_format=frame["out_format"], idct_split=int(args.split), qco=qco,
+                 **frame["params"])
     st = J.validate_maps_host(p, frame)
     assert st == 0, st
     ctx = J.Context(0)
     df = J.DeviceFrame(frame)
-    bufs = [ctx.empty_xyb(p), ctx.empty_xyb(p)]
+    # with the quantization constraint the reconstruction (bufs[0]) is kept
+    # and the passes alternate between bufs[1] and bufs[2]
+    bufs = [ctx.empty_xyb(p) for _ in range(3 if qco else 2)]
     info = ctx.empty_info(p)
     out = ctx.empty_out(p)
     stream = torch.cuda.current_stream()
     n_epf = p.epf_iters
 
     def step(evs):
-        # block info + reconstruct -> EPF passes -> Gaborish + XYB -> RGB; an
-        # event after each
+        # block info + reconstruct -> EPF passes (-> quantization constraint)
+        # -> Gaborish + XYB -> RGB; an event after each
         evs[0].record(stream)
         ctx.block_info(p, df, info, stream=stream)
         ctx.reconstruct(p, df, info, bufs[0], stream=stream)
         evs[1].record(stream)
         cur = 0
         for i in range(n_epf):
-            ctx.epf_pass(p, df, info, bufs[cur], bufs[1 - cur], stream=stream)
-            cur = 1 - cur
+            dst = (2 if i & 1 else 1) if qco else 1 - cur
+            ctx.epf_pass(p, df, info, bufs[cur], bufs[dst], stream=stream)
+            cur = dst
             evs[2 + i].record(stream)
+        if qco:
+            ctx.qco_pass(p, df, info, bufs[0], bufs[cur], stream=stream)
+            evs[2 + n_epf].record(stream)
         ctx.finish(p, df, bufs[cur], out, stream=stream)
-        evs[2 + n_epf].record(stream)
+        evs[-1].record(stream)
 
-    n_ev = 3 + n_epf
+    n_ev = 3 + n_epf + qco
     mk = lambda: [torch.cuda.Event(enable_timing=True) for _ in range(n_ev)]
     warm = mk()
     for _ in range(args.warmup):
@@ -176,11 +187,15 @@ def bench_frame(args, J, wl, torch, np):
     lat = [e[0].elapsed_time(e[-1]) for e in events]
     recon_ms = statistics.mean(e[0].elapsed_time(e[1]) for e in events)
     epf_ms = [statistics.mean(e[1 + i].elapsed_time(e[2 + i]) for e in events) for i in range(n_epf)]
-    fin_ms = statistics.mean(e[1 + n_epf].elapsed_time(e[2 + n_epf]) for e in events)
+    qco_ms = (statistics.mean(e[1 + n_epf].elapsed_time(e[2 + n_epf]) for e in events)
+              if qco else None)
+    fin_ms = statistics.mean(e[-2].elapsed_time(e[-1]) for e in events)
     mp = W * H / 1e6
     value = mp / (ms_per_step / 1e3)
     log(f"bench: {ms_per_step:.4f} ms/step, {value:.1f} MP/s; recon {recon_ms:.4f} ms, "
-        f"epf {['%.4f' % x for x in epf_ms]} ms, finish {fin_ms:.4f} ms")
+        f"epf {['%.4f' % x for x in epf_ms]} ms, "
+        + (f"qco {qco_ms:.4f} ms ({W * H * QCO_BYTES_PER_PX / qco_ms / 1e6:.0f} GB/s), "
+           if qco else "") + f"finish {fin_ms:.4f} ms")
 
     kernels = kernel_table(W * H, recon_ms, statistics.mean(epf_ms) if n_epf else None, fin_ms,
                            p.out_format, ("recon_kernel", "epf_kernel", "finish_kernel"))
@@ -218,7 +233,7 @@ def bench_frame(args, J, wl, torch, np):
     if not args.no_check or not args.no_cpu_baseline:
         from oracle import oracle as O
         from tests import parity as P
-        q = O.params(W, H, **frame["params"])
+        q = O.params(W, H, qco=qco, **frame["params"])
         log("bench: running the FP64 oracle on the full frame")
         t = time.perf_counter()
         orc = O.decode_stages(q, frame)
@@ -237,7 +252,7 @@ def bench_frame(args, J, wl, torch, np):
         if not args.no_check:
             gpu = P.gpu_stages(ctx, p, df)
             np.testing.assert_array_equal(gpu["out"], out.cpu().numpy())
-            cmp = P.compare_rgb(p, gpu, orc)
+            cmp = P.compare_rgb(p, gpu, orc, frame["strategy"])
             # per transform type: max-abs over that type's pixels outside the
             # flip-affected ones
             names = {0: "DCT8", 1: "IDENTITY", 2: "DCT2", 3: "DCT4", 4: "DCT16", 5: "DCT32",
@@ -258,7 +273,8 @@ def bench_frame(args, J, wl, torch, np):
         "value": round(value, 2),
         "ms_per_step": round(ms_per_step, 5),
         "dtype": "f32",
-        "config": {"workload": frame["name"], "xsize": W, "ysize": H, "epf_iters": n_epf,
+        "config": {"workload": frame["name"] + ("_qco" if qco else ""), "xsize": W, "ysize": H,
+                   "epf_iters": n_epf, "qco": bool(qco),
                    "gaborish": bool(p.gab), "output": "f32 linear RGB / 255",
                    "frames_per_step": 1,
                    "idct": "split bf16 hi+lo on matrix cores, f32 accumulate" if args.split
@@ -267,10 +283,15 @@ def bench_frame(args, J, wl, torch, np):
                        "p99": round(float(np.percentile(lat, 99)), 5)},
         "graph_latency_ms": graph_lat,
         "stage_ms": {"reconstruct": round(recon_ms, 5), "epf": [round(x, 5) for x in epf_ms],
-                     "finish": round(fin_ms, 5)},
+                     **({"qco": round(qco_ms, 5)} if qco else {}), "finish": round(fin_ms, 5)},
         "host_wall_ms_per_step": round(wall / args.steps * 1e3, 5),
         "error": err,
         "roofline": roofline,
+        **({"qco_roofline": dict(
+            bound="hbm", kernel="qco_kernel", bytes_per_px=QCO_BYTES_PER_PX,
+            achieved=round(W * H * QCO_BYTES_PER_PX / qco_ms / 1e6, 1), peak=HBM_PEAK_GBS,
+            unit="GB/s", frac=round(W * H * QCO_BYTES_PER_PX / qco_ms / 1e6 / HBM_PEAK_GBS, 4),
+            avg_ms=round(qco_ms, 5))} if qco else {}),
         "cpu_baseline": cpu,
     }
 
@@ -568,6 +589,8 @@ def main():
     ap.add_argument("--c5-sweep", type=int, default=0,
                     help="serving: number of doubling arrival rates to sweep after the run")
     ap.add_argument("--c5-sweep-seconds", type=float, default=5.0)
+    ap.add_argument("--qco", action="store_true",
+                    help="single-frame workloads: the quantization constraint after the EPF passes")
     ap.add_argument("--split", action="store_true",
                     help="split-precision (bf16 hi+lo matrix-core) inverse transform")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -605,6 +628,10 @@ def main():
                           "launches": 25, "ms_per_copy": round(ms, 4),
                           "copy_GBps": round(2 * n * 4 / ms / 1e6, 1)}))
         return
+    if args.qco and args.workload in ("c4", "c1x1024", "c5"):
+        print(json.dumps({"error": "--qco applies to the single-frame workloads (the batch "
+                                   "stages have no constraint pass)"}))
+        sys.exit(2)
     if args.workload == "c5":
         run = bench_serving
     else:
