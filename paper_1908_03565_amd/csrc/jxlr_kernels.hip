@@ -973,12 +973,16 @@ struct QcoArgs {
   float mul;          // qco_interval_mul
   float dc_step[3];   // qco_interval_mul * DC multiplier
   const DeviceTables* __restrict__ tab;
+  int vec;            // planes and stride allow 16-byte accesses
 };
 
 // One 64x32 tile: every varblock lies inside one of its two 32x32 regions.
 __device__ __attribute__((always_inline)) inline void qco_tile(const QcoArgs& a, int tbx, int tby) {
   __shared__ float coef[3][kRecTH][kRecLd];
   __shared__ float s_acmul[32];
+  // per-axis LLF maps for 1, 2 and 4 DC samples, zero-padded to 4x4:
+  // s_ax[0] DC -> scaled LLF (a16s, a32s), s_ax[1] the inverse (b16s, b32s)
+  __shared__ float s_ax[2][3][4][4];
   __shared__ uint8_t s_owner[2][16], s_strat[2][16];
   __shared__ int s_bad[2];
   __shared__ int s_mma[2];
@@ -994,6 +998,14 @@ __device__ __attribute__((always_inline)) inline void qco_tile(const QcoArgs& a,
     s_bad[tid] = 0;
     s_mma[tid] = -1;
   }
+  if (tid >= 64 && tid < 160) {
+    const int k = tid - 64, inv = k / 48, sz = (k >> 4) % 3, x = (k >> 2) & 3, i = k & 3;
+    const float* m2 = inv ? T->b16s : T->a16s;
+    const float* m4 = inv ? T->b32s : T->a32s;
+    s_ax[inv][sz][x][i] = sz == 0 ? (x == 0 && i == 0 ? 1.0f : 0.0f)
+                        : sz == 1 ? (x < 2 && i < 2 ? m2[x * 2 + i] : 0.0f)
+                                  : m4[x * 4 + i];
+  }
   __syncthreads();
   if (tid < 32) {
     load_tile_info(a.info, a.Wb, a.Hb, gbx0, gby0, tid, s_strat, s_owner, s_bad);
@@ -1002,18 +1014,47 @@ __device__ __attribute__((always_inline)) inline void qco_tile(const QcoArgs& a,
     const float qfv = float(1 + a.qf[in ? size_t(by) * a.map_stride + bx : 0]);
     s_acmul[tid] = 65536.0f / (a.gscale * qfv);
   }
-  // the residual of the filters; samples outside the frame were never
-  // filtered and count as 0
-  for (int i = tid; i < 3 * kRecTH * kRecTW; i += kRecThreads) {
-    const int c = i / (kRecTH * kRecTW), rem = i - c * (kRecTH * kRecTW);
-    const int Y = rem / kRecTW, X = rem - Y * kRecTW;
-    const int gx = x0 + X, gy = y0 + Y;
-    float d = 0.0f;
-    if (gx < a.W && gy < a.H) {
-      const size_t o = c * plane + size_t(gy) * a.stride + gx;
-      d = a.io[o] - a.orig[o];
+  // The residual of the filters, in the reconstruction's groups (4
+  // horizontally adjacent samples of all three channels; all loads of a
+  // thread issued together).  Samples outside the frame were never filtered
+  // and count as 0.
+  {
+    float d[kRecGPT][3][4];
+#pragma unroll
+    for (int k = 0; k < kRecGPT; ++k) {
+      const int g = tid + kRecThreads * k;
+      const int Y = g >> 4, X = 4 * (g & 15), gx = x0 + X, gy = y0 + Y;
+      const size_t o = size_t(gy) * a.stride + gx;
+      if (g < kRecGroups && gy < a.H && a.vec && gx + 4 <= a.W) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const float4 f = *reinterpret_cast<const float4*>(a.io + c * plane + o);
+          const float4 r = *reinterpret_cast<const float4*>(a.orig + c * plane + o);
+          d[k][c][0] = f.x - r.x;
+          d[k][c][1] = f.y - r.y;
+          d[k][c][2] = f.z - r.z;
+          d[k][c][3] = f.w - r.w;
+        }
+      } else {
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+          for (int e = 0; e < 4; ++e)
+            d[k][c][e] = g < kRecGroups && gy < a.H && gx + e < a.W
+                             ? a.io[c * plane + o + e] - a.orig[c * plane + o + e]
+                             : 0.0f;
+      }
     }
-    coef[c][Y][X] = d;
+#pragma unroll
+    for (int k = 0; k < kRecGPT; ++k) {
+      const int g = tid + kRecThreads * k;
+      if (g >= kRecGroups) break;
+      const int Y = g >> 4, X = 4 * (g & 15);
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) coef[c][Y][X + e] = d[k][c][e];
+    }
   }
   __syncthreads();
   if (tid < 2 && s_bad[tid])
@@ -1080,20 +1121,31 @@ __device__ __attribute__((always_inline)) inline void qco_tile(const QcoArgs& a,
   // in the scaled domain).  The corner of each varblock (one thread per
   // varblock and channel): its DC samples from the scaled LLF (b = a^-1 per
   // axis), clamped to +-mul dc_mul, and back (a per axis).
-  for (int i = tid; i < 3 * kRecTH * kRecTW; i += kRecThreads) {
-    const int c = i / (kRecTH * kRecTW), rem = i - c * (kRecTH * kRecTW);
-    const int Y = rem / kRecTW, X = rem - Y * kRecTW, r = X >> 5;
+#pragma unroll
+  for (int k = 0; k < kRecGPT; ++k) {
+    const int g = tid + kRecThreads * k;
+    if (g >= kRecGroups) break;
+    const int Y = g >> 4, X = 4 * (g & 15), r = X >> 5;
     const int lb = (Y >> 3) * 4 + ((X & 31) >> 3);
     const int s = s_strat[r][lb];
     if (s == kAbsent) continue;
     const int o = s_owner[r][lb];
     const int x = (X & 31) - 8 * (o & 3), y = Y - 8 * (o >> 2);
     const int cx = vb_bx(s), cy = vb_by(s);
-    if (x < cx && y < cy) continue;
     const int sz = 64 * cx * cy;
-    const float t = a.mul * s_acmul[(o >> 2) * 8 + 4 * r + (o & 3)] *
-                    T->dqs[dq_off_lut(s) + c * sz + y * 8 * cx + x];
-    coef[c][Y][X] = fminf(fmaxf(coef[c][Y][X], -t), t);
+    const float* dq = T->dqs + dq_off_lut(s) + y * 8 * cx + x;
+    const float m = a.mul * s_acmul[(o >> 2) * 8 + 4 * r + (o & 3)];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const float4 w = *reinterpret_cast<const float4*>(dq + c * sz);
+      const float wv[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        if (x + e < cx && y < cy) continue;  // the LLF corner, below
+        const float t = m * wv[e];
+        coef[c][Y][X + e] = fminf(fmaxf(coef[c][Y][X + e], -t), t);
+      }
+    }
   }
   if (tid < 96) {
     const int c = tid >> 5, b = tid & 31;
@@ -1101,19 +1153,8 @@ __device__ __attribute__((always_inline)) inline void qco_tile(const QcoArgs& a,
     const int s = s_strat[r][lb];
     if (s != kAbsent && s_owner[r][lb] == lb) {
       const int cx = vb_bx(s), cy = vb_by(s);
-      // per-axis maps zero-padded to 4x4 (a 1-sample axis is the identity)
-      auto axis = [&](int n, const float* m2, const float* m4, float (&m)[4][4]) {
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-          for (int j = 0; j < 4; ++j)
-            m[i][j] = n == 4 ? m4[i * 4 + j]
-                     : n == 2 ? (i < 2 && j < 2 ? m2[i * 2 + j] : 0.0f)
-                              : (i == 0 && j == 0 ? 1.0f : 0.0f);
-      };
-      float bx_[4][4], by_[4][4], L[4][4], D[4][4];
-      axis(cx, T->b16s, T->b32s, bx_);
-      axis(cy, T->b16s, T->b32s, by_);
+      const int sx = cx == 4 ? 2 : cx - 1, sy = cy == 4 ? 2 : cy - 1;
+      float L[4][4], D[4][4];
 #pragma unroll
       for (int y = 0; y < 4; ++y)
 #pragma unroll
@@ -1125,7 +1166,7 @@ __device__ __attribute__((always_inline)) inline void qco_tile(const QcoArgs& a,
         for (int i = 0; i < 4; ++i) {
           float acc = 0.0f;
 #pragma unroll
-          for (int x = 0; x < 4; ++x) acc = fmaf(bx_[i][x], L[y][x], acc);
+          for (int x = 0; x < 4; ++x) acc = fmaf(s_ax[1][sx][i][x], L[y][x], acc);
           D[y][i] = acc;
         }
 #pragma unroll
@@ -1134,19 +1175,17 @@ __device__ __attribute__((always_inline)) inline void qco_tile(const QcoArgs& a,
         for (int i = 0; i < 4; ++i) {
           float acc = 0.0f;
 #pragma unroll
-          for (int y = 0; y < 4; ++y) acc = fmaf(by_[j][y], D[y][i], acc);
+          for (int y = 0; y < 4; ++y) acc = fmaf(s_ax[1][sy][j][y], D[y][i], acc);
           L[j][i] = fminf(fmaxf(acc, -a.dc_step[c]), a.dc_step[c]);
         }
       // back: Ay D' Ax^T
-      axis(cx, T->a16s, T->a32s, bx_);
-      axis(cy, T->a16s, T->a32s, by_);
 #pragma unroll
       for (int j = 0; j < 4; ++j)
 #pragma unroll
         for (int x = 0; x < 4; ++x) {
           float acc = 0.0f;
 #pragma unroll
-          for (int i = 0; i < 4; ++i) acc = fmaf(bx_[x][i], L[j][i], acc);
+          for (int i = 0; i < 4; ++i) acc = fmaf(s_ax[0][sx][x][i], L[j][i], acc);
           D[j][x] = acc;
         }
 #pragma unroll
@@ -1155,7 +1194,7 @@ __device__ __attribute__((always_inline)) inline void qco_tile(const QcoArgs& a,
         for (int x = 0; x < 4; ++x) {
           float acc = 0.0f;
 #pragma unroll
-          for (int j = 0; j < 4; ++j) acc = fmaf(by_[y][j], D[j][x], acc);
+          for (int j = 0; j < 4; ++j) acc = fmaf(s_ax[0][sy][y][j], D[j][x], acc);
           if (y < cy && x < cx) coef[c][8 * byl + y][8 * bxl + x] = acc;
         }
     }
@@ -1164,13 +1203,28 @@ __device__ __attribute__((always_inline)) inline void qco_tile(const QcoArgs& a,
 
   inverse_passes(coef, s_strat, s_owner, s_mma, T, tid);
 
-  for (int i = tid; i < 3 * kRecTH * kRecTW; i += kRecThreads) {
-    const int c = i / (kRecTH * kRecTW), rem = i - c * (kRecTH * kRecTW);
-    const int Y = rem / kRecTW, X = rem - Y * kRecTW;
-    const int gx = x0 + X, gy = y0 + Y;
+#pragma unroll
+  for (int k = 0; k < kRecGPT; ++k) {
+    const int g = tid + kRecThreads * k;
+    if (g >= kRecGroups) break;
+    const int Y = g >> 4, X = 4 * (g & 15), gx = x0 + X, gy = y0 + Y;
     if (gx >= a.W || gy >= a.H || s_bad[X >> 5]) continue;
-    const size_t o = c * plane + size_t(gy) * a.stride + gx;
-    a.io[o] = a.orig[o] + coef[c][Y][X];
+    const size_t o = size_t(gy) * a.stride + gx;
+    if (a.vec && gx + 4 <= a.W) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const float4 r = *reinterpret_cast<const float4*>(a.orig + c * plane + o);
+        *reinterpret_cast<float4*>(a.io + c * plane + o) =
+            make_float4(r.x + coef[c][Y][X], r.y + coef[c][Y][X + 1], r.z + coef[c][Y][X + 2],
+                        r.w + coef[c][Y][X + 3]);
+      }
+    } else {
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          if (gx + e < a.W) a.io[c * plane + o + e] = a.orig[c * plane + o + e] + coef[c][Y][X + e];
+    }
   }
 }
 
@@ -1726,7 +1780,7 @@ __global__ __launch_bounds__(kRecThreads, kRecMinBlocks) void recon_kernel(Recon
   const int t = xcd_tile(blockIdx.x, gridDim.x);
   recon_tile(a, t % tiles_x, t / tiles_x);
 }
-__global__ __launch_bounds__(kRecThreads) void qco_kernel(QcoArgs a, int tiles_x) {
+__global__ __launch_bounds__(kRecThreads, 4) void qco_kernel(QcoArgs a, int tiles_x) {
   const int t = xcd_tile(blockIdx.x, gridDim.x);
   qco_tile(a, t % tiles_x, t / tiles_x);
 }
@@ -2298,6 +2352,9 @@ jxlr_status jxlr_qco_pass(jxlr_ctx* ctx, const jxlr_frame_params* p, const jxlr_
   a.mul = p->qco_interval_mul;
   for (int c = 0; c < 3; ++c) a.dc_step[c] = p->qco_interval_mul * p->dc_mul[c];
   a.tab = ctx->tables;
+  a.vec = (stride & 3) == 0 && (size_t(p->ysize) * stride & 3) == 0 &&
+          (reinterpret_cast<uintptr_t>(orig) & 15) == 0 &&
+          (reinterpret_cast<uintptr_t>(xyb_io) & 15) == 0;
   DeviceGuard g(ctx->device);
   if (!g.ok) return JXLR_E_HIP;
   hipLaunchKernelGGL(qco_kernel, dim3(tiles_x(p) * tiles_y(p)), dim3(kRecThreads), 0, stream, a,
