@@ -69,20 +69,22 @@ def log(msg):
 PMC_COPY_SCALE = {"FETCH_SIZE": 2.0, "WRITE_SIZE": 1.0}
 PMC_SOURCES = ("paper_1908_03565_amd/csrc/jxlr_kernels.hip", "paper_1908_03565_amd/csrc/jxlr_tables.cpp",
                "paper_1908_03565_amd/csrc/jxlr_tables.h", "paper_1908_03565_amd/csrc/gen_dct_consts.py")
-PMC_SOURCES_SHA256 = "d47e408e0a8237f0918f209b0d90aa444c1591597e2a1a4e634f84eb844d6ea8"
+PMC_SOURCES_SHA256 = "d452e449fe0c50b7fef33da888453256334d835cbdcb31c650ce3d3ed7dc0e93"
 # (workload name, kernel) -> (FETCH_SIZE KiB, WRITE_SIZE KiB) per dispatch
 PMC_KIB = {
-    ("c2_2048x2048_mixed_epf2", "epf_kernel"): (25446.9, 49152.0),
-    ("c2_2048x2048_mixed_epf2", "recon_kernel"): (25627.3, 49316.6),
-    ("c2_2048x2048_mixed_epf2", "finish_kernel"): (24913.0, 49152.0),
-    ("c3_4096x4096_half_dct32", "epf_kernel"): (100135.1, 196608.0),
-    ("c3_4096x4096_half_dct32", "recon_kernel"): (100941.7, 196933.1),
-    ("c3_4096x4096_half_dct32", "finish_kernel"): (98929.8, 196608.0),
-    ("c4_batch64_loguniform_256_3072_epf1_u8srgb", "epf_batch_kernel"): (528694.4, 1052226.5),
-    ("c4_batch64_loguniform_256_3072_epf1_u8srgb", "recon_batch_kernel"): (536272.2, 1061301.2),
-    ("c4_batch64_loguniform_256_3072_epf1_u8srgb", "finish_batch_kernel"): (526389.8, 263635.6),
-    ("c1x1024_256x256_dct8", "recon_batch_kernel"): (401006.3, 786433.6),
-    ("c1x1024_256x256_dct8", "finish_batch_kernel"): (845161.7, 786432.0),
+    ("c2_2048x2048_mixed_epf2", "epf_kernel"): (25440.4, 49152.0),
+    ("c2_2048x2048_mixed_epf2", "recon_kernel"): (25796.2, 49481.3),
+    ("c2_2048x2048_mixed_epf2", "finish_kernel"): (24870.3, 49152.0),
+    ("c2_2048x2048_mixed_epf2_qco", "epf_kernel"): (25440.6, 49152.0),
+    ("c2_2048x2048_mixed_epf2_qco", "qco_kernel"): (70786.2, 49152.0),
+    ("c3_4096x4096_half_dct32", "epf_kernel"): (101222.8, 196608.0),
+    ("c3_4096x4096_half_dct32", "recon_kernel"): (101298.8, 197254.4),
+    ("c3_4096x4096_half_dct32", "finish_kernel"): (98883.4, 196608.0),
+    ("c4_batch64_loguniform_256_3072_epf1_u8srgb", "epf_batch_kernel"): (528697.4, 1052228.1),
+    ("c4_batch64_loguniform_256_3072_epf1_u8srgb", "recon_batch_kernel"): (536292.0, 1061586.0),
+    ("c4_batch64_loguniform_256_3072_epf1_u8srgb", "finish_batch_kernel"): (526398.5, 263629.0),
+    ("c1x1024_256x256_dct8", "recon_batch_kernel"): (401017.0, 786436.0),
+    ("c1x1024_256x256_dct8", "finish_batch_kernel"): (845047.3, 786432.0),
 }
 
 
@@ -199,7 +201,8 @@ def bench_frame(args, J, wl, torch, np):
 
     kernels = kernel_table(W * H, recon_ms, statistics.mean(epf_ms) if n_epf else None, fin_ms,
                            p.out_format, ("recon_kernel", "epf_kernel", "finish_kernel"))
-    roofline = roofline_of(kernels, {"epf_kernel": n_epf}, frame["name"], W * H)
+    wname = frame["name"] + ("_qco" if qco else "")
+    roofline = roofline_of(kernels, {"epf_kernel": n_epf}, wname, W * H)
 
     graph_lat = None
     if args.workload == "c1":
@@ -291,7 +294,7 @@ def bench_frame(args, J, wl, torch, np):
             bound="hbm", kernel="qco_kernel", bytes_per_px=QCO_BYTES_PER_PX,
             achieved=round(W * H * QCO_BYTES_PER_PX / qco_ms / 1e6, 1), peak=HBM_PEAK_GBS,
             unit="GB/s", frac=round(W * H * QCO_BYTES_PER_PX / qco_ms / 1e6 / HBM_PEAK_GBS, 4),
-            avg_ms=round(qco_ms, 5))} if qco else {}),
+            avg_ms=round(qco_ms, 5), traffic=traffic_bytes(wname, "qco_kernel"))} if qco else {}),
         "cpu_baseline": cpu,
     }
 

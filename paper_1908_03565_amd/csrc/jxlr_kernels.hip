@@ -827,7 +827,7 @@ struct Dct2<1> {
 // Inverse of segment_dct<N>: x_k = (k ? 2 : 1) / N * DCT-II(y)_k (the scale
 // is a power of two, so exact).
 template <int N>
-__device__ inline void segment_fwd(float* v, int st) {
+__device__ __attribute__((always_inline)) inline void segment_fwd(float* v, int st) {
   float r[N];
 #pragma unroll
   for (int k = 0; k < N; ++k) r[k] = v[k * st];
@@ -838,7 +838,7 @@ __device__ inline void segment_fwd(float* v, int st) {
 
 // Inverse of segment_dct4: the first and second halves go back to the even
 // and the odd positions.
-__device__ inline void segment_fwd4(float* v, int st) {
+__device__ __attribute__((always_inline)) inline void segment_fwd4(float* v, int st) {
   float a[4], b[4];
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
@@ -854,7 +854,7 @@ __device__ inline void segment_fwd4(float* v, int st) {
   }
 }
 
-__device__ inline void segment_inv(float* v, int st, bool four, int n) {
+__device__ __attribute__((always_inline)) inline void segment_inv(float* v, int st, bool four, int n) {
   if (four) segment_fwd4(v, st);
   else if (n == 8) segment_fwd<8>(v, st);
   else if (n == 16) segment_fwd<16>(v, st);
