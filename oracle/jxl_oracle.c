@@ -75,6 +75,7 @@ void orc_params_default(orc_params* p, int32_t xsize, int32_t ysize) {
   p->target_nits_div50 = 5;  /* A.4.5 */
   p->qco = 0;                 /* C.10: qco defaults to false */
   p->qco_interval_mul = 0.5;
+  p->ac_prediction = 0;
 }
 
 int orc_num_threads(void) {
@@ -603,6 +604,83 @@ int orc_dc_from_llf(int s, const double* llf, double* dc) {
   return ORC_OK;
 }
 
+/* I.2.6 with N = 4: the 2cy x 2cx image of a varblock's 4x4-pixel cells from
+ * its LLF coefficients (cy x cx), the other coefficients taken as 0.  DCT
+ * family (I.2.6.2): the top 2cy x 2cx coefficients scaled by
+ * ScaleF(bysize, 2cy, y) ScaleF(bxsize, 2cx, x), then the 2cy x 2cx IDCT_2D.
+ * 8x8 types (I.2.6.3): the four cells take the DC. */
+int orc_dc2x2_from_llf(int s, const double* llf, double* out) {
+  int32_t bx, by;
+  if (!supported(s) || !orc_varblock_size(s, &bx, &by)) return ORC_E_STRATEGY;
+  if (!is_dct_family(s)) {
+    for (int i = 0; i < 4; ++i) out[i] = llf[0];
+    return ORC_OK;
+  }
+  const int32_t cx = bx / 8, cy = by / 8, cx4 = 2 * cx, cy4 = 2 * cy;
+  double L[64];
+  for (int32_t y = 0; y < cy4; ++y)
+    for (int32_t x = 0; x < cx4; ++x)
+      L[y * cx4 + x] = (x < cx && y < cy)
+                           ? llf[y * cx + x] * orc_scalef(by, cy4, y) * orc_scalef(bx, cx4, x)
+                           : 0.0;
+  idct_2d(cx4, cy4, L, out);
+  return ORC_OK;
+}
+
+/* I.2.7 with N = 4: the top 2cy x 2cx coefficients of a varblock from its
+ * 2cy x 2cx image of 4x4-pixel cells.  DCT family (I.2.7.2 at N = 4, with the
+ * division by the number of cells as in R2): C = DCT_2D(in), out(x, y) =
+ * C(x, y) ScaleF(2cy, bysize, y) ScaleF(2cx, bxsize, x) / (4 cx cy).  8x8
+ * types (I.2.7.3): AuxDCT2x2(in, 2) for Identity, DCT2, DCT4 and AFV; for
+ * DCT8x4 and DCT4x8 the two printed forms.  Readings: the first form
+ * printed for "DCT 8 x 4" (pairs along columns, the scaled differences down
+ * the rows) is DCT8x4, whose DC pair is (0, 0) and (1, 0); the second, also
+ * labelled "DCT 8 x 4", is DCT4x8 (DC pair (0, 0), (0, 1)), with its
+ * "block11" read as coef4 = in(1, 1).  Only this assignment makes the
+ * 4x4-cell means of the inverse transform equal the input (the property the
+ * other types have), which the tests pin. */
+int orc_llf2x2_from_dc2x2(int s, const double* in, double* out) {
+  int32_t bx, by;
+  if (!supported(s) || !orc_varblock_size(s, &bx, &by)) return ORC_E_STRATEGY;
+  if (!is_dct_family(s)) {
+    /* in / out are 2 x 2, entry (x, y) at [y * 2 + x] */
+    const double c00 = in[0], c01 = in[1], c10 = in[2], c11 = in[3];
+    if (s == ORC_DCT8X4 || s == ORC_DCT4X8) {
+      const double sf = orc_scalef(2, 8, 1);
+      if (s == ORC_DCT8X4) {
+        const double dc0 = (c00 + c10) / 2, ac0 = (c00 - c10) / 2;
+        const double dc1 = (c01 + c11) / 2, ac1 = (c01 - c11) / 2;
+        out[0] = (dc0 + dc1) / 2;
+        out[1] = (dc0 - dc1) / 2;
+        out[2] = ac0 * sf;
+        out[3] = ac1 * sf;
+      } else {
+        const double dc0 = (c00 + c01) / 2, ac0 = (c00 - c01) / 2;
+        const double dc1 = (c10 + c11) / 2, ac1 = (c10 - c11) / 2;
+        out[0] = (dc0 + dc1) / 2;
+        out[2] = (dc0 - dc1) / 2;
+        out[1] = ac0 * sf;
+        out[3] = ac1 * sf;
+      }
+      return ORC_OK;
+    }
+    /* AuxDCT2x2(in, 2): block(x, y) = in[y * 2 + x] */
+    out[0] = (c00 + c01 + c10 + c11) / 4;
+    out[1] = (c00 + c01 - c10 - c11) / 4;
+    out[2] = (c00 - c01 + c10 - c11) / 4;
+    out[3] = (c00 - c01 - c10 + c11) / 4;
+    return ORC_OK;
+  }
+  const int32_t cx4 = bx / 4, cy4 = by / 4;
+  double C[64];
+  fdct_2d(cx4, cy4, in, C);
+  for (int32_t y = 0; y < cy4; ++y)
+    for (int32_t x = 0; x < cx4; ++x)
+      out[y * cx4 + x] = C[y * cx4 + x] * orc_scalef(cy4, by, y) * orc_scalef(cx4, bx, x) /
+                         (double)(cx4 * cy4);
+  return ORC_OK;
+}
+
 /* ======================================================================= */
 /* Dequantization matrices (C.6.1, defaults C.6.1.1)                       */
 /* ======================================================================= */
@@ -833,6 +911,15 @@ int orc_dequant_matrix(int s, int c, double* out) {
 /* Reconstruction: F.2, F.3, Annex G, I.2.7, I.2.4                         */
 /* ======================================================================= */
 
+/* 6.5: mirrored index into [0, size). */
+static int32_t mirror(int32_t coord, int32_t size) {
+  while (coord < 0 || coord >= size) {
+    if (coord < 0) coord = -coord - 1;
+    else coord = 2 * size - 1 - coord;
+  }
+  return coord;
+}
+
 typedef struct {
   int32_t bx0, by0; /* top-left block */
   int s;
@@ -923,6 +1010,77 @@ void orc_dc_smooth(const orc_params* p, int32_t Wb, int32_t Hb, double* dcq) {
   free(src);
 }
 
+/* Annex H, the image step: per channel and per group of 32 x 32 blocks
+ * (groups of 256 x 256 samples, 6.2; the DC2x2 image of a group of gw x gh
+ * blocks is (2 gw + 4) x (2 gh + 4)), the 2x2 cells of each varblock from its
+ * LLF (I.2.6, N = 4), a border of two cells from the ring of DC samples
+ * around the group (mirrored at the frame edge, 6.5), then the adaptive
+ * smoothing of every cell inside the border: the 3x3 weighted average
+ * (0.12 centre, 0.2 edge, 0.02 diagonal neighbours) of the unsmoothed cells
+ * replaces the cell when within 1.7 dcq of it.  The smoothed cells are
+ * stored in out [3][2 Hb][2 Wb] (cell (2 bx + i, 2 by + j) of block (bx, by)).
+ * Readings: the DC samples are the ones the LLF is computed from (after
+ * F.2 smoothing and the DC chroma from luma); dcq is the DC multiplier over
+ * 2^extra_levels, as in F.2; "xsize x ysize" of a group counts blocks. */
+void orc_ac_prediction_image(const orc_params* p, int32_t Wb, int32_t Hb,
+                             const uint8_t* strategy, const double* dcq, double* out) {
+  const int32_t W2 = 2 * Wb;
+  double* img = (double*)malloc(sizeof(double) * 68 * 68);
+  double* sm = (double*)malloc(sizeof(double) * 68 * 68);
+  if (!img || !sm) { free(img); free(sm); return; }
+  for (int c = 0; c < 3; ++c) {
+    const double* d = dcq + (size_t)c * Wb * Hb;
+    const double q = p->dc_mul[c] / (double)(1 << p->extra_levels[c]);
+    for (int32_t gy0 = 0; gy0 < Hb; gy0 += 32)
+      for (int32_t gx0 = 0; gx0 < Wb; gx0 += 32) {
+        const int32_t gw = Wb - gx0 < 32 ? Wb - gx0 : 32, gh = Hb - gy0 < 32 ? Hb - gy0 : 32;
+        const int32_t iw = 2 * gw + 4;
+        /* border ring, then the varblocks inside */
+        for (int32_t by = gy0 - 1; by <= gy0 + gh; ++by)
+          for (int32_t bx = gx0 - 1; bx <= gx0 + gw; ++bx) {
+            if (by >= gy0 && by < gy0 + gh && bx >= gx0 && bx < gx0 + gw) continue;
+            const double v = d[(size_t)mirror(by, Hb) * Wb + mirror(bx, Wb)];
+            for (int j = 0; j < 2; ++j)
+              for (int i = 0; i < 2; ++i)
+                img[(2 + 2 * (by - gy0) + j) * iw + 2 + 2 * (bx - gx0) + i] = v;
+          }
+        for (int32_t by = gy0; by < gy0 + gh; ++by)
+          for (int32_t bx = gx0; bx < gx0 + gw; ++bx) {
+            const int s = strategy[by * Wb + bx];
+            int32_t vbx, vby;
+            orc_varblock_size(s, &vbx, &vby);
+            const int32_t cx = vbx / 8, cy = vby / 8;
+            if (bx % cx || by % cy) continue; /* not a top-left block */
+            double D[16], L[16], out4[64];
+            const int32_t lx = is_dct_family(s) ? cx : 1, ly = is_dct_family(s) ? cy : 1;
+            for (int32_t j = 0; j < cy; ++j)
+              for (int32_t i = 0; i < cx; ++i) D[j * cx + i] = d[(size_t)(by + j) * Wb + bx + i];
+            orc_llf_from_dc(s, D, L);
+            orc_dc2x2_from_llf(s, L, out4);
+            for (int32_t j = 0; j < 2 * ly; ++j)
+              for (int32_t i = 0; i < 2 * lx; ++i)
+                img[(2 + 2 * (by - gy0) + j) * iw + 2 + 2 * (bx - gx0) + i] = out4[j * 2 * lx + i];
+          }
+        for (int32_t y = 2; y < 2 * gh + 2; ++y)
+          for (int32_t x = 2; x < 2 * gw + 2; ++x) {
+            const double* r0 = img + (y - 1) * iw + x;
+            const double* r1 = img + y * iw + x;
+            const double* r2 = img + (y + 1) * iw + x;
+            const double sv = r1[0];
+            const double wa = 0.12 * sv + 0.2 * (r0[0] + r1[-1] + r1[1] + r2[0]) +
+                              0.02 * (r0[-1] + r0[1] + r2[-1] + r2[1]);
+            sm[y * iw + x] = (sv - 1.7 * q <= wa && wa <= sv + 1.7 * q) ? wa : sv;
+          }
+        for (int32_t y = 0; y < 2 * gh; ++y)
+          for (int32_t x = 0; x < 2 * gw; ++x)
+            out[(size_t)c * W2 * 2 * Hb + (size_t)(2 * gy0 + y) * W2 + 2 * gx0 + x] =
+                sm[(y + 2) * iw + x + 2];
+      }
+  }
+  free(img);
+  free(sm);
+}
+
 int orc_reconstruct(const orc_params* p, const int32_t* const ac[3], const int32_t* const dc[3],
                     const uint8_t* strategy, const uint8_t* qf_minus_1, const float* cfl_kx,
                     const float* cfl_kb, double* xyb) {
@@ -956,11 +1114,18 @@ int orc_reconstruct(const orc_params* p, const int32_t* const ac[3], const int32
     dcq[0 * Wb * Hb + i] += p->kx_dc * Y;
     dcq[2 * Wb * Hb + i] += p->kb_dc * Y;
   }
+  /* Annex H: the smoothed 2x2-cell image, when AC prediction is on */
+  double* pred = NULL;
+  if (p->ac_prediction) {
+    pred = (double*)malloc(sizeof(double) * 3 * 4 * (size_t)Wb * Hb);
+    if (!pred) { free(dq); free(dcq); free(list); free(pad); return ORC_E_SIZE; }
+  }
 
   int32_t nvb = 0;
   /* The quant field values are bytes, inside the [0, 256) range of C.5.5. */
   st = scan_varblocks(Wb, Hb, strategy, list, &nvb, NULL);
-  if (st) { free(dq); free(dcq); free(list); free(pad); return st; }
+  if (st) { free(dq); free(dcq); free(list); free(pad); free(pred); return st; }
+  if (pred) orc_ac_prediction_image(p, Wb, Hb, strategy, dcq, pred);
 
 #pragma omp parallel for schedule(dynamic, 16)
   for (int32_t v = 0; v < nvb; ++v) {
@@ -999,6 +1164,24 @@ int orc_reconstruct(const orc_params* p, const int32_t* const ac[3], const int32
         K[0][y * bx + x] += kx * Y;
         K[2][y * bx + x] += kb * Y;
       }
+    /* Annex H: the top (2 lx) x (2 ly) coefficients from the varblock's cells
+     * of the smoothed image (I.2.7, N = 4) are added, the LLF corner (lx x ly)
+     * excepted.  Reading: the cells come from DC samples that already carry
+     * the DC chroma from luma, so the sums are added after Annex G. */
+    if (pred) {
+      const int32_t lx = is_dct_family(vb.s) ? cx : 1, ly = is_dct_family(vb.s) ? cy : 1;
+      for (int c = 0; c < 3; ++c) {
+        double cell[64], P[64];
+        for (int32_t j = 0; j < 2 * ly; ++j)
+          for (int32_t i = 0; i < 2 * lx; ++i)
+            cell[j * 2 * lx + i] =
+                pred[(size_t)c * 4 * Wb * Hb + (size_t)(2 * vb.by0 + j) * 2 * Wb + 2 * vb.bx0 + i];
+        orc_llf2x2_from_dc2x2(vb.s, cell, P);
+        for (int32_t y = 0; y < 2 * ly; ++y)
+          for (int32_t x = 0; x < 2 * lx; ++x)
+            if (x >= lx || y >= ly) K[c][y * bx + x] += P[y * 2 * lx + x];
+      }
+    }
     /* Annex I: inverse transform, written at the varblock's pixels. */
     for (int c = 0; c < 3; ++c) {
       double S[1024];
@@ -1019,6 +1202,7 @@ int orc_reconstruct(const orc_params* p, const int32_t* const ac[3], const int32
   free(dcq);
   free(list);
   free(pad);
+  free(pred);
   return ORC_OK;
 }
 
@@ -1026,13 +1210,6 @@ int orc_reconstruct(const orc_params* p, const int32_t* const ac[3], const int32
 /* Mirroring (6.5)                                                         */
 /* ======================================================================= */
 
-static int32_t mirror(int32_t coord, int32_t size) {
-  while (coord < 0 || coord >= size) {
-    if (coord < 0) coord = -coord - 1;
-    else coord = 2 * size - 1 - coord;
-  }
-  return coord;
-}
 
 /* ======================================================================= */
 /* Edge-preserving filter (J.2)                                            */

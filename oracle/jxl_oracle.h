@@ -74,6 +74,7 @@ typedef struct {
   int32_t dc_smoothing;        /* adaptive DC smoothing of F.2; 0 = skipped */
   int32_t qco;                 /* loop_filter.qco (C.10): J.3 after the EPF passes */
   double  qco_interval_mul;    /* loop_filter.qco_interval_mul (C.10) */
+  int32_t ac_prediction;       /* Annex H (kSkipPredictLF clear); 0 = skipped */
 } orc_params;
 
 /* Fills the defaults the draft gives for every field (C.4, C.10, L.2, A.4.5). */
@@ -104,6 +105,10 @@ int orc_llf_from_dc(int strategy, const double* dc, double* llf);
 /* Downsampled image from LF coefficients (I.2.6, N = 8): llf [cy][cx] -> dc [cy][cx]. */
 int orc_dc_from_llf(int strategy, const double* llf, double* dc);
 
+/* The same at N = 4 (Annex H): llf [cy][cx] -> cells [2cy][2cx] (8x8 types:
+ * 2 x 2), and cells -> the top [2cy][2cx] coefficients (I.2.7, N = 4). */
+int orc_dc2x2_from_llf(int strategy, const double* llf, double* cells);
+int orc_llf2x2_from_dc2x2(int strategy, const double* cells, double* coeffs);
 /* ---- dequantization (C.6.1, F.3) --------------------------------------- */
 /* Default dequantization matrix of a transform type and channel, [by][bx]. */
 int orc_dequant_matrix(int strategy, int c, double* out);
@@ -111,6 +116,10 @@ int orc_dequant_matrix(int strategy, int c, double* out);
 /* ---- reconstruction (F, G, I) ------------------------------------------ */
 /* Quantized DC/AC planes and side maps -> XYB samples, cropped to xsize x ysize.
  * cfl_kx/cfl_kb: per 64x64 tile kX and kB of Annex G, [ceil(ysize/64)][ceil(xsize/64)]. */
+/* Annex H image step: the smoothed 2x2-cell image [3][2Hb][2Wb] of a frame
+ * from its DC samples [3][Hb][Wb] (after F.2 and the DC chroma from luma). */
+void orc_ac_prediction_image(const orc_params* p, int32_t Wb, int32_t Hb,
+                             const uint8_t* strategy, const double* dcq, double* out);
 /* F.2 adaptive DC smoothing of a dequantized DC image [3][Hb][Wb], in place. */
 void orc_dc_smooth(const orc_params* p, int32_t Wb, int32_t Hb, double* dcq);
 int orc_reconstruct(const orc_params* p,

@@ -37,6 +37,7 @@ class OrcParams(C.Structure):
         ("dc_smoothing", C.c_int32),
         ("qco", C.c_int32),
         ("qco_interval_mul", C.c_double),
+        ("ac_prediction", C.c_int32),
     ]
 
 
@@ -67,6 +68,9 @@ def lib():
         L.orc_forward_transform.argtypes = [C.c_int, _f64p, _f64p]
         L.orc_llf_from_dc.argtypes = [C.c_int, _f64p, _f64p]
         L.orc_dc_from_llf.argtypes = [C.c_int, _f64p, _f64p]
+        L.orc_dc2x2_from_llf.argtypes = [C.c_int, _f64p, _f64p]
+        L.orc_llf2x2_from_dc2x2.argtypes = [C.c_int, _f64p, _f64p]
+        L.orc_ac_prediction_image.argtypes = [P, C.c_int32, C.c_int32, _u8p, _f64p, _f64p]
         L.orc_dequant_matrix.argtypes = [C.c_int, C.c_int, _f64p]
         L.orc_afv_basis.argtypes = [_f64p]
         L.orc_dc_smooth.argtypes = [P, C.c_int32, C.c_int32, _f64p]
@@ -185,6 +189,41 @@ def dc_from_llf(s, llf):
     L = np.ascontiguousarray(llf, dtype=np.float64).reshape(cy, cx)
     out = np.zeros((cy, cx))
     _check(lib().orc_dc_from_llf(s, L, out))
+    return out
+
+
+def _lf_shape(s):
+    bx, by = varblock_size(s)
+    if s not in (0, 4, 5, 6, 7, 8, 9, 10, 11):
+        return 1, 1
+    return bx // 8, by // 8
+
+
+def dc2x2_from_llf(s, llf):
+    """I.2.6 at N = 4: LLF (cy, cx) -> cells (2cy, 2cx)."""
+    cx, cy = _lf_shape(s)
+    L = np.ascontiguousarray(llf, dtype=np.float64).reshape(cy, cx)
+    out = np.zeros((2 * cy, 2 * cx))
+    _check(lib().orc_dc2x2_from_llf(s, L, out))
+    return out
+
+
+def llf2x2_from_dc2x2(s, cells):
+    """I.2.7 at N = 4: cells (2cy, 2cx) -> the top (2cy, 2cx) coefficients."""
+    cx, cy = _lf_shape(s)
+    D = np.ascontiguousarray(cells, dtype=np.float64).reshape(2 * cy, 2 * cx)
+    out = np.zeros((2 * cy, 2 * cx))
+    _check(lib().orc_llf2x2_from_dc2x2(s, D, out))
+    return out
+
+
+def ac_prediction_image(p, strategy, dcq):
+    """Annex H image step: smoothed cells (3, 2Hb, 2Wb) from DC (3, Hb, Wb)."""
+    d = np.ascontiguousarray(dcq, dtype=np.float64)
+    Hb, Wb = d.shape[1], d.shape[2]
+    out = np.zeros((3, 2 * Hb, 2 * Wb))
+    lib().orc_ac_prediction_image(C.byref(p), Wb, Hb,
+                                  np.ascontiguousarray(strategy, np.uint8), d, out)
     return out
 
 

@@ -627,6 +627,149 @@ def test_dc_smoothing_keeps_samples_far_from_the_average():
 
 
 # --------------------------------------------------------------------------
+# AC prediction (Annex H; I.2.6 / I.2.7 at N = 4)
+# --------------------------------------------------------------------------
+
+def _cell_means(S, cy4, cx4):
+    return S.reshape(cy4, S.shape[0] // cy4, cx4, S.shape[1] // cx4).mean(axis=(1, 3))
+
+
+@pytest.mark.parametrize("s", DCT_FAMILY + EIGHT_CLASS)
+def test_dc2x2_is_cell_mean_of_lf_reconstruction(s):
+    # I.2.6 at N = 4: the 4x4-pixel cell means of the varblock decoded from
+    # its LLF alone (for the 8x8 types the LF reconstruction is the DC)
+    bx, by = O.varblock_size(s)
+    lx, ly = (bx // 8, by // 8) if s in DCT_FAMILY else (1, 1)
+    L = _rng(60 + s).standard_normal((ly, lx))
+    K = np.zeros((by, bx))
+    K[:ly, :lx] = L
+    S = O.inverse_transform(s, K)
+    np.testing.assert_allclose(O.dc2x2_from_llf(s, L), _cell_means(S, 2 * ly, 2 * lx), atol=1e-12)
+
+
+@pytest.mark.parametrize("s", DCT_FAMILY + EIGHT_CLASS)
+def test_llf2x2_reproduces_cell_means(s):
+    # I.2.7 at N = 4: the top 2cy x 2cx coefficients it gives, decoded alone,
+    # have exactly the input as their 4x4-pixel cell means.  For DCT4x8 and
+    # DCT8x4 this holds only with each printed form on its own type.
+    bx, by = O.varblock_size(s)
+    lx, ly = (bx // 8, by // 8) if s in DCT_FAMILY else (1, 1)
+    cells = _rng(70 + s).standard_normal((2 * ly, 2 * lx))
+    P = O.llf2x2_from_dc2x2(s, cells)
+    K = np.zeros((by, bx))
+    K[:2 * ly, :2 * lx] = P
+    S = O.inverse_transform(s, K)
+    np.testing.assert_allclose(_cell_means(S, 2 * ly, 2 * lx), cells, atol=1e-12)
+    # and I.2.7 undoes I.2.6 on an LLF: the LLF back, zeros elsewhere
+    L = _rng(80 + s).standard_normal((ly, lx))
+    back = O.llf2x2_from_dc2x2(s, O.dc2x2_from_llf(s, L))
+    np.testing.assert_allclose(back[:ly, :lx], L, atol=1e-12)
+    back[:ly, :lx] = 0.0
+    assert np.abs(back).max() < 1e-12
+
+
+def _brute_cells(d, q):
+    """Annex H image step for a frame of 8x8 types in one group, written with
+    numpy / scipy: cells = the DC repeated 2x2, a border of two cells from the
+    mirrored DC ring, the 3x3 average with weights 0.12 / 0.2 / 0.02 taken
+    where within 1.7 q."""
+    pad = np.pad(d, 1, mode="symmetric")
+    img = np.kron(pad, np.ones((2, 2)))
+    k = np.array([[0.02, 0.2, 0.02], [0.2, 0.12, 0.2], [0.02, 0.2, 0.02]])
+    wa = ndi.correlate(img, k, mode="nearest")
+    ok = np.abs(wa - img) <= 1.7 * q
+    return np.where(ok, wa, img)[2:-2, 2:-2]
+
+
+def test_ac_prediction_image_brute_force():
+    # one group of 8x8 types with mirrored borders, against the numpy form
+    Hb, Wb = 7, 11
+    rng = _rng(90)
+    strat = rng.choice([0, 1, 2, 3, 12, 13, 14], size=(Hb, Wb)).astype(np.uint8)
+    q = (0.5, 1.0, 2.0)
+    p = O.params(8 * Wb, 8 * Hb, dc_mul=q, ac_prediction=1)
+    d = np.stack([rng.integers(-3, 4, size=(Hb, Wb)) * qq for qq in q]).astype(np.float64)
+    got = O.ac_prediction_image(p, strat, d)
+    for c in range(3):
+        want = _brute_cells(d[c], q[c])
+        np.testing.assert_allclose(got[c], want, atol=1e-12)
+        assert np.abs(want - np.kron(d[c], np.ones((2, 2)))).max() > 0.1  # smoothing acted
+
+
+def test_ac_prediction_groups_read_the_dc_ring():
+    # two groups side by side: a DC change in the first block column of the
+    # right group reaches the left group's last cells (through the ring);
+    # one deeper inside does not
+    Hb, Wb = 8, 64
+    strat = np.zeros((Hb, Wb), np.uint8)
+    p = O.params(8 * Wb, 8 * Hb, dc_mul=(1.0, 1.0, 1.0), ac_prediction=1)
+    d = _rng(91).integers(-1, 2, size=(3, Hb, Wb)).astype(np.float64)
+    base = O.ac_prediction_image(p, strat, d)
+    d1 = d.copy()
+    d1[:, 3, 32] += 1.0
+    near = O.ac_prediction_image(p, strat, d1)
+    assert np.abs(near[:, :, 63] - base[:, :, 63]).max() > 0.01
+    d2 = d.copy()
+    d2[:, 3, 40] += 1.0
+    far = O.ac_prediction_image(p, strat, d2)
+    np.testing.assert_array_equal(far[:, :, :64], base[:, :, :64])
+
+
+@pytest.mark.parametrize("mixed", [False, True])
+def test_ac_prediction_in_reconstruction(mixed):
+    # frames of 8x8 types: the prediction adds, per block, coefficients whose
+    # cell means are the smoothed cells minus their mean (the DC stays), so
+    # the reconstruction's cell means become DC + cells - mean(cells); the
+    # DC image carries the DC chroma from luma
+    Hb, Wb = 6, 9
+    rng = _rng(92 + mixed)
+    strat = (rng.choice([0, 1, 2, 3, 12, 13, 14], size=(Hb, Wb)) if mixed
+             else np.zeros((Hb, Wb))).astype(np.uint8)
+    dc = rng.integers(-3, 4, size=(3, Hb, Wb))
+    f = _frame_of(0, 8 * Wb, 8 * Hb, dc, kx=0.0, kb=0.0)
+    f["strategy"] = strat
+    kw = dict(dc_mul=(0.5, 1.0, 2.0), kx_dc=0.25, kb_dc=-0.5)
+    p1 = O.params(8 * Wb, 8 * Hb, ac_prediction=1, **kw)
+    p0 = O.params(8 * Wb, 8 * Hb, **kw)
+    x1, x0 = O.reconstruct(p1, f), O.reconstruct(p0, f)
+    assert np.abs(x1 - x0).max() > 1e-2  # the prediction is active
+    dq = dc * np.array(kw["dc_mul"])[:, None, None]
+    dq[0] += 0.25 * dq[1]
+    dq[2] += -0.5 * dq[1]
+    for c in range(3):
+        q = kw["dc_mul"][c]
+        cells = _brute_cells(dq[c], q)
+        blockmean = np.kron(cells.reshape(Hb, 2, Wb, 2).mean(axis=(1, 3)), np.ones((2, 2)))
+        want = np.kron(dq[c], np.ones((2, 2))) + cells - blockmean
+        np.testing.assert_allclose(_cell_means(x1[c], 2 * Hb, 2 * Wb), want, atol=1e-10)
+        np.testing.assert_allclose(_cell_means(x0[c], 2 * Hb, 2 * Wb), np.kron(dq[c], np.ones((2, 2))),
+                                   atol=1e-10)
+
+
+def test_ac_prediction_leaves_unsmoothed_frames_alone():
+    # no cell passes the 1.7 dcq window (a DC checkerboard of amplitude 10
+    # dcq) or every average equals its cell (constant DC): the prediction
+    # adds nothing, whatever the types
+    Hb, Wb = 8, 8
+    y, x = np.mgrid[0:Hb, 0:Wb]
+    strat = np.zeros((Hb, Wb), np.uint8)
+    strat[0:4, 0:4] = 5
+    strat[4:6, 0:2] = 4
+    strat[0:4, 4:8] = np.array([[1, 2, 3, 12], [13, 14, 0, 1], [2, 3, 12, 13], [14, 0, 0, 3]])
+    for dc in (np.where((x + y) % 2 == 0, 10, -10)[None].repeat(3, 0),
+               np.full((3, Hb, Wb), 7)):
+        f = _frame_of(0, 64, 64, dc)
+        f["strategy"] = strat
+        if dc.std() > 0:
+            f["strategy"] = np.where(np.isin(strat, [4, 5]), 0, strat).astype(np.uint8)
+        f["ac"] = _rng(93).integers(-3, 4, size=f["ac"].shape).astype(np.int32)
+        kw = dict(dc_mul=(1.0, 1.0, 1.0))
+        x1 = O.reconstruct(O.params(64, 64, ac_prediction=1, **kw), f)
+        x0 = O.reconstruct(O.params(64, 64, **kw), f)
+        np.testing.assert_allclose(x1, x0, atol=1e-9)
+
+
+# --------------------------------------------------------------------------
 # Quantization constraint (J.3)
 # --------------------------------------------------------------------------
 
