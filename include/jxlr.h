@@ -118,6 +118,17 @@ typedef struct {
    * The batch functions reject it (JXLR_E_PARAM). */
   int32_t  qco;
   float    qco_interval_mul;  /* C.10 default 0.5; finite, >= 0 */
+  /* AC prediction of Annex H (1) or not (0, the default; the draft's
+   * kSkipPredictLF case): per group of 256x256 samples an image of 2x2 cells
+   * per block (I.2.6 at N = 4 of each varblock's LLF, a border from the DC
+   * ring around the group, mirrored at the frame edge), adaptively smoothed
+   * (0.12 / 0.2 / 0.02 weights, accepted within 1.7 dc_mul[c]; extra_levels
+   * must be 0), then I.2.7 at N = 4 gives each varblock's top 2cy x 2cx
+   * coefficients, which are added (LLF corner excepted) after the chroma
+   * from luma.  Needs io->ac_pred for jxlr_reconstruct (filled by
+   * jxlr_ac_prediction); jxlr_decode manages it.  The batch functions reject
+   * it (JXLR_E_PARAM). */
+  int32_t  ac_prediction;
 } jxlr_frame_params;
 
 /* Input and output planes of one frame.  With Wb = ceil(xsize/8),
@@ -152,6 +163,10 @@ typedef struct {
   size_t cfl_stride;
   void* out[3];
   size_t out_stride;
+  /* Annex H sums, float [3][2*Hb][2*Wb] (row stride 2*Wb), written by
+   * jxlr_ac_prediction and read by jxlr_reconstruct when p->ac_prediction;
+   * may be NULL otherwise. */
+  const float* ac_pred;
 } jxlr_frame_io;
 
 typedef struct jxlr_ctx jxlr_ctx;
@@ -202,6 +217,16 @@ jxlr_status jxlr_decode(jxlr_ctx* ctx, const jxlr_frame_params* p, const jxlr_fr
  * set. */
 jxlr_status jxlr_block_info(jxlr_ctx* ctx, const jxlr_frame_params* p, const jxlr_frame_io* io,
                             uint8_t* info, hipStream_t stream);
+
+/* Annex H: the predicted sums of every varblock's low coefficients from the
+ * DC planes and `info` (F.2 smoothing and DC chroma from luma applied as in
+ * the reconstruction) into pred, float [3][2*Hb][2*Wb] in device memory owned
+ * by the caller: block (bx, by) holds, at (2 bx + i, 2 by + j), its varblock's
+ * coefficient (2 dx + i, 2 dy + j) ((dx, dy): the block's offset inside the
+ * varblock; 0 in the LLF corner), scaled like the library's dequantization
+ * tables.  Applies whether or not p->ac_prediction is set. */
+jxlr_status jxlr_ac_prediction(jxlr_ctx* ctx, const jxlr_frame_params* p, const jxlr_frame_io* io,
+                               const uint8_t* info, float* pred, hipStream_t stream);
 
 /* F.2, F.3, Annex G, I.2.7, I.2.4 and the crop of 6.2: coefficient planes of
  * io -> XYB samples, with the varblocks of `info`.  io->out and

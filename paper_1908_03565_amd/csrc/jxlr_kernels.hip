@@ -272,6 +272,35 @@ __device__ inline void afv_inverse(float* base, int ld, const float (*__restrict
   }
 }
 
+// F.2: the dequantized DC of block (bx, by) (plane offset d; `in`: inside the
+// frame), adaptively smoothed from its unsmoothed 3x3 neighbourhood when
+// `smooth` and the block is not on the frame's border (read from the planes),
+// then Annex G with the DC factors; out = X, Y, B.
+__device__ __attribute__((always_inline)) inline void block_dc(
+    const int32_t* const (&dc)[3], size_t dc_stride, int Wb, int Hb, const float (&dc_mul)[3],
+    int smooth, float kx_dc, float kb_dc, int bx, int by, bool in, size_t d, float (&out)[3]) {
+  const float dv0 = float(dc[0][d]), dv1 = float(dc[1][d]), dv2 = float(dc[2][d]);
+  float x_ = dc_mul[0] * dv0, y_ = dc_mul[1] * dv1, b_ = dc_mul[2] * dv2;
+  if (smooth && in && bx > 0 && by > 0 && bx + 1 < Wb && by + 1 < Hb) {
+    float* v[3] = {&x_, &y_, &b_};
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const int32_t* p0 = dc[c] + d - dc_stride;
+      const int32_t* p1 = dc[c] + d;
+      const int32_t* p2 = dc[c] + d + dc_stride;
+      const float e = float(p0[0]) + float(p1[-1]) + float(p1[1]) + float(p2[0]);
+      const float g = float(p0[-1]) + float(p0[1]) + float(p2[-1]) + float(p2[1]);
+      const float sv = *v[c], q = dc_mul[c];
+      const float wa = fmaf(0.05226273532324128f, sv,
+                            q * fmaf(0.20345139757231578f, e, 0.0334829185968739f * g));
+      if (sv - 0.5f * q <= wa && wa <= sv + 0.5f * q) *v[c] = wa;
+    }
+  }
+  out[0] = fmaf(kx_dc, y_, x_);
+  out[1] = y_;
+  out[2] = fmaf(kb_dc, y_, b_);
+}
+
 struct ReconArgs {
   int W, H, Wb, Hb;
   const int32_t* ac[3];
@@ -294,6 +323,7 @@ struct ReconArgs {
   const DeviceTables* __restrict__ tab;
   int split;        // split-precision matrix-core transform of uniform regions
   int dc_smooth;    // adaptive DC smoothing (F.2); dcq = dc_mul
+  const float* pred;  // AC prediction sums [3][2 Hb][2 Wb] (Annex H), or null
   int ac_vec;       // AC planes and stride allow 16-byte loads
   int xyb_vec;      // XYB planes and stride allow 16-byte stores
 };
@@ -627,34 +657,16 @@ __device__ __attribute__((always_inline)) inline void recon_tile(const ReconArgs
     // blocks outside the frame read block (0, 0) and are discarded
     const size_t m = in ? size_t(by) * a.map_stride + bx : 0;
     const size_t d = in ? size_t(by) * a.dc_stride + bx : 0;
-    const float dv0 = float(a.dc[0][d]), dv1 = float(a.dc[1][d]), dv2 = float(a.dc[2][d]);
     const float qfv = float(1 + a.qf[m]);
-    float x_ = a.dc_mul[0] * dv0, y_ = a.dc_mul[1] * dv1, b_ = a.dc_mul[2] * dv2;
-    if (a.dc_smooth && in && bx > 0 && by > 0 && bx + 1 < a.Wb && by + 1 < a.Hb) {
-      // F.2 adaptive smoothing of the dequantized DC, per channel, from the
-      // unsmoothed 3x3 neighbourhood (read from the planes: it may leave the
-      // tile)
-      float* v[3] = {&x_, &y_, &b_};
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        const int32_t* p0 = a.dc[c] + d - a.dc_stride;
-        const int32_t* p1 = a.dc[c] + d;
-        const int32_t* p2 = a.dc[c] + d + a.dc_stride;
-        const float e = float(p0[0]) + float(p1[-1]) + float(p1[1]) + float(p2[0]);
-        const float g = float(p0[-1]) + float(p0[1]) + float(p2[-1]) + float(p2[1]);
-        const float sv = *v[c], q = a.dc_mul[c];
-        const float wa = fmaf(0.05226273532324128f, sv,
-                              q * fmaf(0.20345139757231578f, e, 0.0334829185968739f * g));
-        if (sv - 0.5f * q <= wa && wa <= sv + 0.5f * q) *v[c] = wa;
-      }
-    }
+    float v3[3];
+    block_dc(a.dc, a.dc_stride, a.Wb, a.Hb, a.dc_mul, a.dc_smooth, a.kx_dc, a.kb_dc, bx, by, in, d,
+             v3);
     // C.5.5: AcMul = 2^16 / (global_scale * (1 + dv)); the product is an
     // integer below 2^24, so one rounding.
     s_acmul[tid] = in ? 65536.0f / (a.gscale * qfv) : 0.0f;
-    // Annex G on the DC samples, with the DC factors
-    s_dc[0][tid] = in ? fmaf(a.kx_dc, y_, x_) : 0.0f;
-    s_dc[1][tid] = in ? y_ : 0.0f;
-    s_dc[2][tid] = in ? fmaf(a.kb_dc, y_, b_) : 0.0f;
+    s_dc[0][tid] = in ? v3[0] : 0.0f;
+    s_dc[1][tid] = in ? v3[1] : 0.0f;
+    s_dc[2][tid] = in ? v3[2] : 0.0f;
   }
   __syncthreads();
   if (tid < 2) {
@@ -740,6 +752,21 @@ __device__ __attribute__((always_inline)) inline void recon_tile(const ReconArgs
         acc = fmaf(s_llw[sy][dy][jy], row, acc);
       }
       coef[c][8 * oy + dy][32 * r + 8 * ox + dx] = acc;
+      if (a.pred) {
+        // Annex H: the block's 2x2 share of its varblock's predicted sums,
+        // coefficients (2 dx + i, 2 dy + j) (scaled like the tables), the LLF
+        // corner excepted (written above)
+        const size_t w2 = 2 * size_t(a.Wb);
+        const float* pp = a.pred + (size_t(c) * 2 * a.Hb + 2 * (gby0 + byl)) * w2 + 2 * (gbx0 + bxl);
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+          for (int i = 0; i < 2; ++i) {
+            const int x = 2 * dx + i, y = 2 * dy + j;
+            if (x < cxb && y < cyb) continue;
+            coef[c][8 * oy + y][32 * r + 8 * ox + x] += pp[j * w2 + i];
+          }
+      }
     }
   }
   __syncthreads();
@@ -780,6 +807,196 @@ __device__ __attribute__((always_inline)) inline void recon_tile(const ReconArgs
         }
       }
     }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// AC prediction (Annex H).  One workgroup per group of 32x32 blocks: the DC
+// of the group and its ring (mirrored, 6.5), the group's image of 2x2 cells
+// per block (each varblock's cells from its DC through the tables' cell
+// maps; the ring's cells repeat its DC), the adaptive smoothing of the
+// group's cells, and per block its 2x2 share of the varblock's predicted
+// coefficients, written (scaled like the dequantization tables) for the
+// reconstruction to add.
+
+struct PredArgs {
+  int Wb, Hb;
+  const int32_t* dc[3];
+  size_t dc_stride;
+  const uint8_t* info;
+  float dc_mul[3];
+  float kx_dc, kb_dc;
+  int dc_smooth;
+  float* pred;  // [3][2 Hb][2 Wb]
+  const DeviceTables* __restrict__ tab;
+};
+
+constexpr int kPredThreads = 256;
+constexpr int kGroupBlocks = 32;  // 256 samples (6.2)
+constexpr int kCellLd = 2 * kGroupBlocks + 4;
+
+__global__ __launch_bounds__(kPredThreads) void acpred_kernel(PredArgs a, int groups_x) {
+  __shared__ float s_gdc[3][kGroupBlocks + 2][kGroupBlocks + 2];
+  __shared__ float s_cell[3][kCellLd][kCellLd];
+  __shared__ float s_u[3][8][4], s_v[3][8][8];
+  const int tid = threadIdx.x;
+  const int gx0 = kGroupBlocks * (blockIdx.x % groups_x), gy0 = kGroupBlocks * (blockIdx.x / groups_x);
+  const int gw = min(kGroupBlocks, a.Wb - gx0), gh = min(kGroupBlocks, a.Hb - gy0);
+  const DeviceTables* __restrict__ T = a.tab;
+  const float sf = T->pred_sf, s81 = T->pred_s8_1;
+
+  for (int i = tid; i < 3 * 8 * 4; i += kPredThreads) (&s_u[0][0][0])[i] = (&T->pred_u[0][0][0])[i];
+  for (int i = tid; i < 3 * 8 * 8; i += kPredThreads) (&s_v[0][0][0])[i] = (&T->pred_v[0][0][0])[i];
+  // DC of the group and its ring
+  const int rw = gw + 2, rh = gh + 2;
+  for (int i = tid; i < rw * rh; i += kPredThreads) {
+    const int ly = i / rw, lx = i - ly * rw;
+    const int bx = mirror(gx0 - 1 + lx, a.Wb), by = mirror(gy0 - 1 + ly, a.Hb);
+    float v[3];
+    block_dc(a.dc, a.dc_stride, a.Wb, a.Hb, a.dc_mul, a.dc_smooth, a.kx_dc, a.kb_dc, bx, by, true,
+             size_t(by) * a.dc_stride + bx, v);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) s_gdc[c][ly][lx] = v[c];
+  }
+  __syncthreads();
+  // cells: the ring's repeat its DC; each varblock's top-left block fills
+  // the varblock's 2cy x 2cx cells, U_y D U_x^T (8x8 types: the DC)
+  for (int i = tid; i < rw * rh; i += kPredThreads) {
+    const int ly = i / rw, lx = i - ly * rw;
+    const bool ring = lx == 0 || ly == 0 || lx == rw - 1 || ly == rh - 1;
+    int s = 0, cx = 1, cy = 1;
+    if (!ring) {
+      const uint32_t v = a.info[size_t(gy0 + ly - 1) * a.Wb + gx0 + lx - 1];
+      if (v != kInvalid) {
+        if (v & 0xF0u) continue;  // not the top-left block of its varblock
+        s = int(v & 15u);
+        if (s == 0 || (s >= 4 && s <= 11)) {
+          cx = vb_bx(s);
+          cy = vb_by(s);
+        }
+      }
+    }
+    const int mx = cx == 4 ? 2 : cx - 1, my = cy == 4 ? 2 : cy - 1;
+#pragma unroll 1
+    for (int c = 0; c < 3; ++c) {
+      if (cx == 1 && cy == 1) {
+        const float d = s_gdc[c][ly][lx];
+        s_cell[c][2 * ly][2 * lx] = d;
+        s_cell[c][2 * ly][2 * lx + 1] = d;
+        s_cell[c][2 * ly + 1][2 * lx] = d;
+        s_cell[c][2 * ly + 1][2 * lx + 1] = d;
+        continue;
+      }
+      // columns first: t[j][ix] = sum_iy U_y[j][iy] D[iy][ix]
+      float t[8][4];
+#pragma unroll
+      for (int j = 0; j < 8; ++j)
+#pragma unroll
+        for (int ix = 0; ix < 4; ++ix) {
+          float acc = 0.0f;
+#pragma unroll
+          for (int iy = 0; iy < 4; ++iy)
+            if (iy < cy && ix < cx) acc = fmaf(s_u[my][j][iy], s_gdc[c][ly + iy][lx + ix], acc);
+          t[j][ix] = acc;
+        }
+      for (int j = 0; j < 2 * cy; ++j)
+        for (int k = 0; k < 2 * cx; ++k) {
+          float acc = 0.0f;
+#pragma unroll
+          for (int ix = 0; ix < 4; ++ix)
+            if (ix < cx) acc = fmaf(s_u[mx][k][ix], t[j][ix], acc);
+          s_cell[c][2 * ly + j][2 * lx + k] = acc;
+        }
+    }
+  }
+  __syncthreads();
+  // adaptive smoothing of the group's cells (not the ring's), per channel,
+  // from the unsmoothed neighbours
+  const int cw = 2 * gw, ncell = cw * 2 * gh;
+  constexpr int kCellsPerThread = (2 * kGroupBlocks) * (2 * kGroupBlocks) / kPredThreads;
+#pragma unroll 1
+  for (int c = 0; c < 3; ++c) {
+    const float q = a.dc_mul[c];
+    float nv[kCellsPerThread];
+#pragma unroll
+    for (int k = 0; k < kCellsPerThread; ++k) {
+      const int i = tid + kPredThreads * k;
+      nv[k] = 0.0f;
+      if (i < ncell) {
+        const int y = 2 + i / cw, x = 2 + i % cw;
+        const float sv = s_cell[c][y][x];
+        const float e = (s_cell[c][y - 1][x] + s_cell[c][y + 1][x]) + (s_cell[c][y][x - 1] + s_cell[c][y][x + 1]);
+        const float g = (s_cell[c][y - 1][x - 1] + s_cell[c][y - 1][x + 1]) +
+                        (s_cell[c][y + 1][x - 1] + s_cell[c][y + 1][x + 1]);
+        const float wa = fmaf(0.12f, sv, fmaf(0.2f, e, 0.02f * g));
+        nv[k] = (sv - 1.7f * q <= wa && wa <= sv + 1.7f * q) ? wa : sv;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kCellsPerThread; ++k) {
+      const int i = tid + kPredThreads * k;
+      if (i < ncell) s_cell[c][2 + i / cw][2 + i % cw] = nv[k];
+    }
+  }
+  __syncthreads();
+  // per block and channel: its 2x2 share (2 dx + i, 2 dy + j) of the
+  // varblock's predicted coefficients from the varblock's cells S
+  // (DCT family: V_y S V_x^T; 8x8 types: the I.2.7.3 forms), the LLF
+  // corner set to 0
+  const size_t w2 = 2 * size_t(a.Wb);
+  for (int it = tid; it < 3 * gw * gh; it += kPredThreads) {
+    const int c = it / (gw * gh), b = it - c * (gw * gh);
+    const int ly = b / gw, lx = b - ly * gw;
+    const uint32_t v = a.info[size_t(gy0 + ly) * a.Wb + gx0 + lx];
+    float out[2][2] = {{0.0f, 0.0f}, {0.0f, 0.0f}};
+    if (v != kInvalid) {
+      const int s = int(v & 15u), dx = int((v >> 4) & 3u), dy = int((v >> 6) & 3u);
+      const int ox = 2 + 2 * (lx - dx), oy = 2 + 2 * (ly - dy);  // the varblock's first cell
+      if (s == 0 || (s >= 4 && s <= 11)) {
+        const int cx = vb_bx(s), cy = vb_by(s);
+        const int mx = cx == 4 ? 2 : cx - 1, my = cy == 4 ? 2 : cy - 1;
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+          for (int i = 0; i < 2; ++i) {
+            const int x = 2 * dx + i, y = 2 * dy + j;
+            if (x < cx && y < cy) continue;
+            float acc = 0.0f;
+            for (int r = 0; r < 2 * cy; ++r) {
+              float row = 0.0f;
+              for (int k = 0; k < 2 * cx; ++k) row = fmaf(s_v[mx][x][k], s_cell[c][oy + r][ox + k], row);
+              acc = fmaf(s_v[my][y][r], row, acc);
+            }
+            out[j][i] = acc;
+          }
+      } else {
+        const float c00 = s_cell[c][oy][ox], c01 = s_cell[c][oy][ox + 1];
+        const float c10 = s_cell[c][oy + 1][ox], c11 = s_cell[c][oy + 1][ox + 1];
+        if (s == 13) {  // DCT8x4: DC pair (0, 0), (1, 0)
+          const float dc0 = 0.5f * (c00 + c10), ac0 = 0.5f * (c00 - c10);
+          const float dc1 = 0.5f * (c01 + c11), ac1 = 0.5f * (c01 - c11);
+          out[0][1] = 0.5f * (dc0 - dc1);
+          out[1][0] = ac0 * sf * s81;
+          out[1][1] = ac1 * sf * s81;
+        } else if (s == 12) {  // DCT4x8: DC pair (0, 0), (0, 1)
+          const float dc0 = 0.5f * (c00 + c01), ac0 = 0.5f * (c00 - c01);
+          const float dc1 = 0.5f * (c10 + c11), ac1 = 0.5f * (c10 - c11);
+          out[1][0] = 0.5f * (dc0 - dc1);
+          out[0][1] = ac0 * sf * s81;
+          out[1][1] = ac1 * sf * s81;
+        } else {  // AuxDCT2x2(cells, 2)
+          out[0][1] = 0.25f * ((c00 + c01) - (c10 + c11));
+          out[1][0] = 0.25f * ((c00 - c01) + (c10 - c11));
+          out[1][1] = 0.25f * ((c00 - c01) - (c10 - c11));
+        }
+      }
+    }
+    float* dst = a.pred + (size_t(c) * 2 * a.Hb + 2 * (gy0 + ly)) * w2 + 2 * (gx0 + lx);
+    dst[0] = out[0][0];
+    dst[1] = out[0][1];
+    dst[w2] = out[1][0];
+    dst[w2 + 1] = out[1][1];
   }
 }
 
@@ -1957,6 +2174,8 @@ jxlr_status check_params(const jxlr_frame_params* p) {
   const bool el0 = p->extra_levels[0] == 0 && p->extra_levels[1] == 0 && p->extra_levels[2] == 0;
   if (p->dc_smoothing && !el0) return JXLR_E_PARAM;
   if (p->qco < 0 || p->qco > 1) return JXLR_E_PARAM;
+  if (p->ac_prediction < 0 || p->ac_prediction > 1 || (p->ac_prediction && !el0))
+    return JXLR_E_PARAM;
   if (p->qco && (!el0 || !(p->qco_interval_mul >= 0.0f) || !std::isfinite(p->qco_interval_mul)))
     return JXLR_E_PARAM;
   return JXLR_OK;
@@ -2022,6 +2241,7 @@ jxlr_status jxlr_params_default(jxlr_frame_params* p, uint32_t xsize, uint32_t y
   p->epf_sigma_shift = 0;
   p->qco = 0;
   p->qco_interval_mul = 0.5f;
+  p->ac_prediction = 0;
   const float m[9] = {2542.56835937500000f, -2326.53173828125000f, 44.17734527587891f,
                       -698.04852294921875f, 1012.71777343750000f,  -76.22974395751953f,
                       -827.36480712890625f, 709.83502197265625f,   451.38488769531250f};
@@ -2111,13 +2331,19 @@ int xyb_buffers(const jxlr_frame_params* p) {
   if (p->epf_iters == 0) return 1;
   return p->qco && p->epf_iters > 1 ? 3 : 2;
 }
+// Annex H sums, when AC prediction is on.
+size_t pred_bytes(const jxlr_frame_params* p) {
+  return p->ac_prediction ? round256(size_t(12) * sizeof(float) * blocks_of(p->xsize) *
+                                     blocks_of(p->ysize))
+                          : 0;
+}
 }  // namespace
 
 extern "C" {
 
 size_t jxlr_workspace_bytes(const jxlr_frame_params* p) {
   if (check_params(p) != JXLR_OK) return 0;
-  return info_bytes(p) + xyb_buffers(p) * xyb_bytes(p);
+  return info_bytes(p) + xyb_buffers(p) * xyb_bytes(p) + pred_bytes(p);
 }
 
 }  // extern "C"
@@ -2180,6 +2406,11 @@ jxlr_status make_recon_args(jxlr_ctx* ctx, const jxlr_frame_params* p, const jxl
   a.tab = ctx->tables;
   a.split = p->idct_split;
   a.dc_smooth = p->dc_smoothing;
+  a.pred = nullptr;
+  if (p->ac_prediction) {
+    if (!io->ac_pred) return JXLR_E_NULL;
+    a.pred = io->ac_pred;
+  }
   {
     bool av = (io->ac_stride & 3) == 0;
     for (int c = 0; c < 3; ++c) av = av && (reinterpret_cast<uintptr_t>(io->ac[c]) & 15) == 0;
@@ -2323,6 +2554,39 @@ jxlr_status jxlr_epf_pass(jxlr_ctx* ctx, const jxlr_frame_params* p, const jxlr_
   return launch_status(hipGetLastError());
 }
 
+jxlr_status jxlr_ac_prediction(jxlr_ctx* ctx, const jxlr_frame_params* p, const jxlr_frame_io* io,
+                               const uint8_t* info, float* pred, hipStream_t stream) {
+  if (!ctx || !info || !pred || !io) return JXLR_E_NULL;
+  jxlr_status st = check_params(p);
+  if (st) return st;
+  for (int c = 0; c < 3; ++c)
+    if (!io->dc[c]) return JXLR_E_NULL;
+  const int Wb = blocks_of(p->xsize), Hb = blocks_of(p->ysize);
+  if (io->dc_stride < size_t(Wb)) return JXLR_E_SIZE;
+  // the smoothing window and the cells' DC need the DC multipliers as the
+  // DcQuantField (extra_levels 0)
+  if (p->extra_levels[0] || p->extra_levels[1] || p->extra_levels[2]) return JXLR_E_PARAM;
+  PredArgs a{};
+  a.Wb = Wb;
+  a.Hb = Hb;
+  for (int c = 0; c < 3; ++c) {
+    a.dc[c] = io->dc[c];
+    a.dc_mul[c] = p->dc_mul[c];
+  }
+  a.dc_stride = io->dc_stride;
+  a.info = info;
+  a.kx_dc = p->kx_dc;
+  a.kb_dc = p->kb_dc;
+  a.dc_smooth = p->dc_smoothing;
+  a.pred = pred;
+  a.tab = ctx->tables;
+  const int gx = (Wb + kGroupBlocks - 1) / kGroupBlocks, gy = (Hb + kGroupBlocks - 1) / kGroupBlocks;
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return JXLR_E_HIP;
+  hipLaunchKernelGGL(acpred_kernel, dim3(gx * gy), dim3(kPredThreads), 0, stream, a, gx);
+  return launch_status(hipGetLastError());
+}
+
 jxlr_status jxlr_qco_pass(jxlr_ctx* ctx, const jxlr_frame_params* p, const jxlr_frame_io* io,
                           const uint8_t* info, const float* orig, float* xyb_io, size_t stride,
                           hipStream_t stream) {
@@ -2389,8 +2653,14 @@ jxlr_status jxlr_decode(jxlr_ctx* ctx, const jxlr_frame_params* p, const jxlr_fr
   for (int i = 0; i < 3; ++i)
     buf[i] = reinterpret_cast<float*>(base + info_bytes(p) + size_t(i) * xyb_bytes(p));
   const size_t stride = p->xsize;
+  jxlr_frame_io iop = *io;
   if ((st = jxlr_block_info(ctx, p, io, info, stream))) return st;
-  if ((st = jxlr_reconstruct(ctx, p, io, info, buf[0], stride, stream))) return st;
+  if (p->ac_prediction) {
+    float* pred = reinterpret_cast<float*>(base + info_bytes(p) + xyb_buffers(p) * xyb_bytes(p));
+    if ((st = jxlr_ac_prediction(ctx, p, io, info, pred, stream))) return st;
+    iop.ac_pred = pred;
+  }
+  if ((st = jxlr_reconstruct(ctx, p, &iop, info, buf[0], stride, stream))) return st;
   // the passes alternate between two buffers; with the quantization
   // constraint the reconstruction in buf[0] stays untouched
   const bool qco = p->qco && p->epf_iters > 0;
@@ -2496,7 +2766,7 @@ extern "C" {
 size_t jxlr_batch_workspace_bytes(int n, const jxlr_frame_params* p) {
   if (n <= 0 || !p) return 0;
   for (int i = 0; i < n; ++i)
-    if (check_params(&p[i]) != JXLR_OK || p[i].qco) return 0;
+    if (check_params(&p[i]) != JXLR_OK || p[i].qco || p[i].ac_prediction) return 0;
   return batch_layout(n, p).total;
 }
 
@@ -2508,7 +2778,8 @@ jxlr_status jxlr_batch_prepare(jxlr_ctx* ctx, int n, const jxlr_frame_params* p,
   for (int i = 0; i < n; ++i) {
     jxlr_status st = check_params(&p[i]);
     if (st) return st;
-    if (p[i].qco) return JXLR_E_PARAM;  // the batch stages have no constraint pass
+    // the batch stages have no constraint pass and no prediction stage
+    if (p[i].qco || p[i].ac_prediction) return JXLR_E_PARAM;
   }
   const BatchLayout L = batch_layout(n, p);
   if (ws_bytes < L.total) return JXLR_E_WORKSPACE;

@@ -496,6 +496,51 @@ bool build_tables(DeviceTables* t) {
     for (int i = 0; i < n; ++i)
       for (int x = 0; x < n; ++x) b[i * n + x] = float(a[i][n + x]);
   }
+  // AC prediction maps, one axis of 8 n pixels.  The side decoded from its
+  // lowest coefficients (the inverse matrix T_N, N = 8 n) is averaged over
+  // 4-pixel cells: W[j][k] = mean of T_N[4 j .. 4 j + 3][k], k < 2 n.  Cells
+  // from DC: U = W[:, :n] A with A the LLF-from-DC axis map (1 for n = 1).
+  // Coefficients from cells: V = W^-1 (Gauss-Jordan), rows scaled by s_N(k).
+  for (int m = 0; m < 3; ++m) {
+    const int n = 1 << m, N = 8 * n, c2 = 2 * n;
+    std::vector<double> T(N * N);
+    inverse_transform_matrix_f64(N, T.data());
+    double W[8][16] = {};
+    for (int j = 0; j < c2; ++j)
+      for (int k = 0; k < c2; ++k) {
+        double acc = 0.0;
+        for (int r = 0; r < 4; ++r) acc += T[(4 * j + r) * N + k];
+        W[j][k] = acc / 4.0;
+      }
+    for (int j = 0; j < c2; ++j)
+      for (int i = 0; i < n; ++i) {
+        double acc = 0.0;
+        for (int k = 0; k < n; ++k) {
+          const double a = n == 1 ? 1.0 : scale_i(n, k) * ortho(n, i, k) * scale_f(n, 8 * n, k);
+          acc += W[j][k] * a;
+        }
+        t->pred_u[m][j][i] = float(acc);
+      }
+    for (int j = 0; j < c2; ++j) W[j][c2 + j] = 1.0;
+    for (int col = 0; col < c2; ++col) {
+      int piv = col;
+      for (int r = col + 1; r < c2; ++r)
+        if (std::fabs(W[r][col]) > std::fabs(W[piv][col])) piv = r;
+      if (!(std::fabs(W[piv][col]) > 0.0)) return false;
+      for (int j = 0; j < 2 * c2; ++j) std::swap(W[col][j], W[piv][j]);
+      const double d = W[col][col];
+      for (int j = 0; j < 2 * c2; ++j) W[col][j] /= d;
+      for (int r = 0; r < c2; ++r)
+        if (r != col) {
+          const double f = W[r][col];
+          for (int j = 0; j < 2 * c2; ++j) W[r][j] -= f * W[col][j];
+        }
+    }
+    for (int k = 0; k < c2; ++k)
+      for (int j = 0; j < c2; ++j) t->pred_v[m][k][j] = float(W[k][c2 + j] * transform_scale(N, k));
+  }
+  t->pred_sf = float(scale_f(2, 8, 1));
+  t->pred_s8_1 = float(transform_scale(8, 1));
   build_mfma_operands(t);
   for (int j = 0; j < 16; ++j)
     for (int i = 0; i < 16; ++i) t->afv[j][i] = float(kAfvBasis[j][i]);

@@ -86,6 +86,18 @@ struct DeviceTables {
   // (quantization constraint, J.3).
   float b16s[2 * 2];
   float b32s[4 * 4];
+  // AC prediction (Annex H), one axis of a varblock side of 8 n pixels
+  // (m = 0, 1, 2 for n = 1, 2, 4 DC samples): pred_u[m][j][i], the mean of
+  // 4-pixel cell j of the side decoded from its LLF, from DC sample i
+  // (I.2.7 then I.2.6 at N = 4); pred_v[m][k][j], coefficient k < 2n from
+  // the 2n cells (I.2.7 at N = 4, the inverse of the cell means of the
+  // lowest 2n frequencies), times the scale s_N(k) of the passes.
+  float pred_u[3][8][4];
+  float pred_v[3][8][8];
+  // ScaleF(2, 8, 1) of the DCT4x8 / DCT8x4 forms of I.2.7.3, and the pass
+  // scale s_8(1) of their 8-point axis.
+  float pred_sf;
+  float pred_s8_1;
 };
 
 // Fills t on the host.  Returns false if a dequantization matrix entry is not

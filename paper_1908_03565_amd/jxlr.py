@@ -43,6 +43,7 @@ class FrameParams(C.Structure):
         ("dc_smoothing", C.c_int32),
         ("qco", C.c_int32),
         ("qco_interval_mul", C.c_float),
+        ("ac_prediction", C.c_int32),
     ]
 
 
@@ -54,6 +55,7 @@ class FrameIO(C.Structure):
         ("map_stride", C.c_size_t),
         ("cfl_kx", C.c_void_p), ("cfl_kb", C.c_void_p), ("cfl_stride", C.c_size_t),
         ("out", C.c_void_p * 3), ("out_stride", C.c_size_t),
+        ("ac_pred", C.c_void_p),
     ]
 
 
@@ -107,6 +109,8 @@ _SIGS = {
     "jxlr_epf_pass": ([C.c_void_p, C.POINTER(FrameParams), C.POINTER(FrameIO), C.c_void_p,
                        C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p, C.c_void_p],
                       C.c_int),
+    "jxlr_ac_prediction": ([C.c_void_p, C.POINTER(FrameParams), C.POINTER(FrameIO), C.c_void_p,
+                            C.c_void_p, C.c_void_p], C.c_int),
     "jxlr_qco_pass": ([C.c_void_p, C.POINTER(FrameParams), C.POINTER(FrameIO), C.c_void_p,
                        C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p], C.c_int),
     "jxlr_finish": ([C.c_void_p, C.POINTER(FrameParams), C.POINTER(FrameIO), C.c_void_p,
@@ -231,8 +235,9 @@ class DeviceFrame:
             setattr(c, k, getattr(self, k).clone())
         return c
 
-    def io(self, out=None):
+    def io(self, out=None, ac_pred=None):
         io = FrameIO()
+        io.ac_pred = ac_pred.data_ptr() if ac_pred is not None else None
         for c in range(3):
             io.ac[c] = self.ac[c].data_ptr()
             io.dc[c] = self.dc[c].data_ptr()
@@ -299,9 +304,19 @@ class Context:
         _check(lib().jxlr_block_info(self.handle, C.byref(p), C.byref(df.io()), info.data_ptr(),
                                      _stream_handle(stream)), "block_info")
 
-    def reconstruct(self, p, df, info, xyb, stream=None):
-        _check(lib().jxlr_reconstruct(self.handle, C.byref(p), C.byref(df.io()), info.data_ptr(),
-                                      xyb.data_ptr(), xyb.shape[2], _stream_handle(stream)),
+    def empty_pred(self, p):
+        import torch
+        Hb, Wb = (p.ysize + 7) // 8, (p.xsize + 7) // 8
+        return torch.empty((3, 2 * Hb, 2 * Wb), dtype=torch.float32, device=f"cuda:{self.device}")
+
+    def ac_prediction(self, p, df, info, pred, stream=None):
+        _check(lib().jxlr_ac_prediction(self.handle, C.byref(p), C.byref(df.io()), info.data_ptr(),
+                                        pred.data_ptr(), _stream_handle(stream)), "ac_prediction")
+
+    def reconstruct(self, p, df, info, xyb, stream=None, pred=None):
+        _check(lib().jxlr_reconstruct(self.handle, C.byref(p), C.byref(df.io(ac_pred=pred)),
+                                      info.data_ptr(), xyb.data_ptr(), xyb.shape[2],
+                                      _stream_handle(stream)),
                "reconstruct")
 
     def epf_pass(self, p, df, info, xyb_in, xyb_out, guide=None, sigma=None, stream=None):

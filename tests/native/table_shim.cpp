@@ -32,4 +32,8 @@ int shim_buckets() { return jxlr::kSrgbBuckets; }
 const float* shim_afv() { return &g_tables.afv[0][0]; }
 const float* shim_b16s() { return g_tables.b16s; }
 const float* shim_b32s() { return g_tables.b32s; }
+const float* shim_pred_u() { return &g_tables.pred_u[0][0][0]; }
+const float* shim_pred_v() { return &g_tables.pred_v[0][0][0]; }
+float shim_pred_sf() { return g_tables.pred_sf; }
+float shim_pred_s8_1() { return g_tables.pred_s8_1; }
 }

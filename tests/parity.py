@@ -66,7 +66,11 @@ def gpu_stages(ctx, p, df):
     info = ctx.empty_info(p)
     ctx.block_info(p, df, info)
     xyb = ctx.empty_xyb(p)
-    ctx.reconstruct(p, df, info, xyb)
+    pred = None
+    if p.ac_prediction:
+        pred = ctx.empty_pred(p)
+        ctx.ac_prediction(p, df, info, pred)
+    ctx.reconstruct(p, df, info, xyb, pred=pred)
     res = {"recon": xyb.cpu().numpy(), "epf": []}
     Hb, Wb = (p.ysize + 7) // 8, (p.xsize + 7) // 8
     cur = xyb

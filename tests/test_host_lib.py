@@ -99,6 +99,12 @@ def test_parameter_ranges():
         assert J.validate_maps_host(p, f) == 7, kw
         assert J.workspace_bytes(p) == 0, kw
     assert J.validate_maps_host(J.params(64, 64, qco=1, qco_interval_mul=0.0), f) == 0
+    # AC prediction: a flag, with the DC multipliers as the DcQuantField
+    for kw in (dict(ac_prediction=2), dict(ac_prediction=1, extra_levels=(0, 0, 2))):
+        p = J.params(64, 64, **kw)
+        assert J.validate_maps_host(p, f) == 7, kw
+        assert J.workspace_bytes(p) == 0, kw
+    assert J.params(64, 64).ac_prediction == 0
     d = J.params(64, 64)
     assert d.qco == 0 and d.qco_interval_mul == 0.5  # C.10 defaults
 
@@ -117,6 +123,9 @@ def test_workspace_bytes():
     assert J.workspace_bytes(J.params(100, 50, epf_iters=2, qco=1)) == J.workspace_bytes(p2) + xyb
     assert J.workspace_bytes(J.params(100, 50, epf_iters=1, qco=1)) == J.workspace_bytes(p2)
     assert J.workspace_bytes(J.params(100, 50, epf_iters=0, qco=1)) == one
+    # AC prediction adds its sums, 3 x 4 floats per block (13 x 7 blocks)
+    extra = J.workspace_bytes(J.params(100, 50, epf_iters=0, ac_prediction=1)) - one
+    assert 12 * 4 * 13 * 7 <= extra < 12 * 4 * 13 * 7 + 256
 
 
 def test_batch_workspace_bytes():
@@ -131,6 +140,7 @@ def test_batch_workspace_bytes():
     assert J.batch_workspace_bytes(ps + [J.params(64, 64, epf_iters=4)]) == 0
     # the batch stages have no constraint pass
     assert J.batch_workspace_bytes(ps + [J.params(64, 64, qco=1)]) == 0
+    assert J.batch_workspace_bytes(ps + [J.params(64, 64, ac_prediction=1)]) == 0
 
 
 # --- the library's constant tables versus the oracle's --------------------
@@ -144,8 +154,11 @@ def shim(tmp_path_factory):
                     os.path.join(csrc, "jxlr_tables.cpp"), "-o", str(out)], check=True)
     L = C.CDLL(str(out))
     for f in ("shim_t8", "shim_t16", "shim_t32", "shim_m4", "shim_a16", "shim_a32", "shim_dq",
-              "shim_dqs", "shim_a16s", "shim_a32s", "shim_b16s", "shim_b32s"):
+              "shim_dqs", "shim_a16s", "shim_a32s", "shim_b16s", "shim_b32s", "shim_pred_u",
+              "shim_pred_v"):
         getattr(L, f).restype = C.POINTER(C.c_float)
+    L.shim_pred_sf.restype = C.c_float
+    L.shim_pred_s8_1.restype = C.c_float
     L.shim_mul.restype = C.POINTER(C.c_int32)
     L.shim_thr.restype = C.POINTER(C.c_float)
     L.shim_mfma.restype = C.POINTER(C.c_uint16)
@@ -259,6 +272,28 @@ def test_dc_from_llf_tables_match_oracle(shim):
         sc = _col_scale(8 * n)[:n]
         ref = np.stack([O.dc_from_llf(s, (e / sc).reshape(1, n)).ravel() for e in np.eye(n)], axis=1)
         np.testing.assert_allclose(b, ref, atol=2e-6)
+
+
+def test_ac_prediction_tables_match_oracle(shim):
+    # pred_u: cells from DC (I.2.7 then I.2.6 at N = 4), pred_v: scaled
+    # coefficients from cells (I.2.7 at N = 4), per axis; their 2-D products
+    # against the oracle's maps for every DCT-family type
+    U = _arr(shim.shim_pred_u(), 3 * 8 * 4).reshape(3, 8, 4)
+    V = _arr(shim.shim_pred_v(), 3 * 8 * 8).reshape(3, 8, 8)
+    m_of = {1: 0, 2: 1, 4: 2}
+    rng = np.random.default_rng(7)
+    for s in (0, 4, 5, 6, 7, 8, 9, 10, 11):
+        bx, by = O.varblock_size(s)
+        cx, cy = bx // 8, by // 8
+        Ux, Uy = U[m_of[cx], :2 * cx, :cx], U[m_of[cy], :2 * cy, :cy]
+        D = rng.standard_normal((cy, cx))
+        np.testing.assert_allclose(Uy @ D @ Ux.T, O.dc2x2_from_llf(s, O.llf_from_dc(s, D)), atol=2e-6)
+        Vx, Vy = V[m_of[cx], :2 * cx, :2 * cx], V[m_of[cy], :2 * cy, :2 * cy]
+        S = rng.standard_normal((2 * cy, 2 * cx))
+        sc = np.outer(_col_scale(by)[:2 * cy], _col_scale(bx)[:2 * cx])
+        np.testing.assert_allclose((Vy @ S @ Vx.T) / sc, O.llf2x2_from_dc2x2(s, S), atol=1e-5)
+    assert shim.shim_pred_sf() == pytest.approx(O.scalef(2, 8, 1), rel=1e-7)
+    assert shim.shim_pred_s8_1() == pytest.approx(_col_scale(8)[1], rel=1e-7)
 
 
 def test_schedule_cache_roundtrip(tmp_path):
