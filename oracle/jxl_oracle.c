@@ -1010,7 +1010,9 @@ void orc_dc_smooth(const orc_params* p, int32_t Wb, int32_t Hb, double* dcq) {
   free(src);
 }
 
-/* Annex H, the image step: per channel and per group of 32 x 32 blocks
+/* Annex H, the image step (margin, if not NULL, receives for each cell the
+ * distance |wa - s| - 1.7 dcq of its smoothing test, negative when taken):
+ * per channel and per group of 32 x 32 blocks
  * (groups of 256 x 256 samples, 6.2; the DC2x2 image of a group of gw x gh
  * blocks is (2 gw + 4) x (2 gh + 4)), the 2x2 cells of each varblock from its
  * LLF (I.2.6, N = 4), a border of two cells from the ring of DC samples
@@ -1023,7 +1025,8 @@ void orc_dc_smooth(const orc_params* p, int32_t Wb, int32_t Hb, double* dcq) {
  * F.2 smoothing and the DC chroma from luma); dcq is the DC multiplier over
  * 2^extra_levels, as in F.2; "xsize x ysize" of a group counts blocks. */
 void orc_ac_prediction_image(const orc_params* p, int32_t Wb, int32_t Hb,
-                             const uint8_t* strategy, const double* dcq, double* out) {
+                             const uint8_t* strategy, const double* dcq, double* out,
+                             double* margin) {
   const int32_t W2 = 2 * Wb;
   double* img = (double*)malloc(sizeof(double) * 68 * 68);
   double* sm = (double*)malloc(sizeof(double) * 68 * 68);
@@ -1070,6 +1073,9 @@ void orc_ac_prediction_image(const orc_params* p, int32_t Wb, int32_t Hb,
             const double wa = 0.12 * sv + 0.2 * (r0[0] + r1[-1] + r1[1] + r2[0]) +
                               0.02 * (r0[-1] + r0[1] + r2[-1] + r2[1]);
             sm[y * iw + x] = (sv - 1.7 * q <= wa && wa <= sv + 1.7 * q) ? wa : sv;
+            if (margin)
+              margin[(size_t)c * W2 * 2 * Hb + (size_t)(2 * gy0 + y - 2) * W2 + 2 * gx0 + x - 2] =
+                  fabs(wa - sv) - 1.7 * q;
           }
         for (int32_t y = 0; y < 2 * gh; ++y)
           for (int32_t x = 0; x < 2 * gw; ++x)
@@ -1125,7 +1131,7 @@ int orc_reconstruct(const orc_params* p, const int32_t* const ac[3], const int32
   /* The quant field values are bytes, inside the [0, 256) range of C.5.5. */
   st = scan_varblocks(Wb, Hb, strategy, list, &nvb, NULL);
   if (st) { free(dq); free(dcq); free(list); free(pad); free(pred); return st; }
-  if (pred) orc_ac_prediction_image(p, Wb, Hb, strategy, dcq, pred);
+  if (pred) orc_ac_prediction_image(p, Wb, Hb, strategy, dcq, pred, NULL);
 
 #pragma omp parallel for schedule(dynamic, 16)
   for (int32_t v = 0; v < nvb; ++v) {

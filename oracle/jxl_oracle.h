@@ -117,9 +117,11 @@ int orc_dequant_matrix(int strategy, int c, double* out);
 /* Quantized DC/AC planes and side maps -> XYB samples, cropped to xsize x ysize.
  * cfl_kx/cfl_kb: per 64x64 tile kX and kB of Annex G, [ceil(ysize/64)][ceil(xsize/64)]. */
 /* Annex H image step: the smoothed 2x2-cell image [3][2Hb][2Wb] of a frame
- * from its DC samples [3][Hb][Wb] (after F.2 and the DC chroma from luma). */
+ * from its DC samples [3][Hb][Wb] (after F.2 and the DC chroma from luma);
+ * margin: each cell's |wa - s| - 1.7 dcq (the smoothing test's distance). */
 void orc_ac_prediction_image(const orc_params* p, int32_t Wb, int32_t Hb,
-                             const uint8_t* strategy, const double* dcq, double* out);
+                             const uint8_t* strategy, const double* dcq, double* out,
+                             double* margin /* [3][2Hb][2Wb] or NULL */);
 /* F.2 adaptive DC smoothing of a dequantized DC image [3][Hb][Wb], in place. */
 void orc_dc_smooth(const orc_params* p, int32_t Wb, int32_t Hb, double* dcq);
 int orc_reconstruct(const orc_params* p,

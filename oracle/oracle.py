@@ -70,7 +70,8 @@ def lib():
         L.orc_dc_from_llf.argtypes = [C.c_int, _f64p, _f64p]
         L.orc_dc2x2_from_llf.argtypes = [C.c_int, _f64p, _f64p]
         L.orc_llf2x2_from_dc2x2.argtypes = [C.c_int, _f64p, _f64p]
-        L.orc_ac_prediction_image.argtypes = [P, C.c_int32, C.c_int32, _u8p, _f64p, _f64p]
+        L.orc_ac_prediction_image.argtypes = [P, C.c_int32, C.c_int32, _u8p, _f64p, _f64p,
+                                              C.c_void_p]
         L.orc_dequant_matrix.argtypes = [C.c_int, C.c_int, _f64p]
         L.orc_afv_basis.argtypes = [_f64p]
         L.orc_dc_smooth.argtypes = [P, C.c_int32, C.c_int32, _f64p]
@@ -217,14 +218,17 @@ def llf2x2_from_dc2x2(s, cells):
     return out
 
 
-def ac_prediction_image(p, strategy, dcq):
-    """Annex H image step: smoothed cells (3, 2Hb, 2Wb) from DC (3, Hb, Wb)."""
+def ac_prediction_image(p, strategy, dcq, want_margin=False):
+    """Annex H image step: smoothed cells (3, 2Hb, 2Wb) from DC (3, Hb, Wb);
+    with want_margin also each cell's |wa - s| - 1.7 dcq."""
     d = np.ascontiguousarray(dcq, dtype=np.float64)
     Hb, Wb = d.shape[1], d.shape[2]
     out = np.zeros((3, 2 * Hb, 2 * Wb))
+    margin = np.zeros((3, 2 * Hb, 2 * Wb))
     lib().orc_ac_prediction_image(C.byref(p), Wb, Hb,
-                                  np.ascontiguousarray(strategy, np.uint8), d, out)
-    return out
+                                  np.ascontiguousarray(strategy, np.uint8), d, out,
+                                  margin.ctypes.data if want_margin else None)
+    return (out, margin) if want_margin else out
 
 
 def dc_smooth(p, dcq):

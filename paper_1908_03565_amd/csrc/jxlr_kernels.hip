@@ -811,13 +811,13 @@ __device__ __attribute__((always_inline)) inline void recon_tile(const ReconArgs
 }
 
 // ---------------------------------------------------------------------------
-// AC prediction (Annex H).  One workgroup per group of 32x32 blocks: the DC
-// of the group and its ring (mirrored, 6.5), the group's image of 2x2 cells
-// per block (each varblock's cells from its DC through the tables' cell
-// maps; the ring's cells repeat its DC), the adaptive smoothing of the
-// group's cells, and per block its 2x2 share of the varblock's predicted
-// coefficients, written (scaled like the dequantization tables) for the
-// reconstruction to add.
+// AC prediction (Annex H).  One workgroup per group of 32x32 blocks and
+// channel: the DC of the group and its ring (mirrored, 6.5), the group's
+// image of 2x2 cells per block (each varblock's cells from its DC through
+// the tables' cell maps; the ring's cells repeat its DC), the adaptive
+// smoothing of the group's cells, and per block its 2x2 share of the
+// varblock's predicted coefficients, written (scaled like the dequantization
+// tables) for the reconstruction to add.
 
 struct PredArgs {
   int Wb, Hb;
@@ -831,23 +831,26 @@ struct PredArgs {
   const DeviceTables* __restrict__ tab;
 };
 
-constexpr int kPredThreads = 256;
+constexpr int kPredThreads = 1024;
 constexpr int kGroupBlocks = 32;  // 256 samples (6.2)
 constexpr int kCellLd = 2 * kGroupBlocks + 4;
 
+// One workgroup per group and channel.
 __global__ __launch_bounds__(kPredThreads) void acpred_kernel(PredArgs a, int groups_x) {
-  __shared__ float s_gdc[3][kGroupBlocks + 2][kGroupBlocks + 2];
-  __shared__ float s_cell[3][kCellLd][kCellLd];
+  __shared__ float s_gdc[kGroupBlocks + 2][kGroupBlocks + 2];
+  __shared__ float s_cell[kCellLd][kCellLd];
   __shared__ float s_u[3][8][4], s_v[3][8][8];
   const int tid = threadIdx.x;
-  const int gx0 = kGroupBlocks * (blockIdx.x % groups_x), gy0 = kGroupBlocks * (blockIdx.x / groups_x);
+  const int c = blockIdx.x % 3, g = blockIdx.x / 3;
+  const int gx0 = kGroupBlocks * (g % groups_x), gy0 = kGroupBlocks * (g / groups_x);
   const int gw = min(kGroupBlocks, a.Wb - gx0), gh = min(kGroupBlocks, a.Hb - gy0);
   const DeviceTables* __restrict__ T = a.tab;
   const float sf = T->pred_sf, s81 = T->pred_s8_1;
 
-  for (int i = tid; i < 3 * 8 * 4; i += kPredThreads) (&s_u[0][0][0])[i] = (&T->pred_u[0][0][0])[i];
-  for (int i = tid; i < 3 * 8 * 8; i += kPredThreads) (&s_v[0][0][0])[i] = (&T->pred_v[0][0][0])[i];
-  // DC of the group and its ring
+  if (tid < 3 * 8 * 4) (&s_u[0][0][0])[tid] = (&T->pred_u[0][0][0])[tid];
+  if (tid < 3 * 8 * 8) (&s_v[0][0][0])[tid] = (&T->pred_v[0][0][0])[tid];
+  // DC of the group and its ring (all three channels for the chroma from
+  // luma; this workgroup keeps channel c)
   const int rw = gw + 2, rh = gh + 2;
   for (int i = tid; i < rw * rh; i += kPredThreads) {
     const int ly = i / rw, lx = i - ly * rw;
@@ -855,8 +858,7 @@ __global__ __launch_bounds__(kPredThreads) void acpred_kernel(PredArgs a, int gr
     float v[3];
     block_dc(a.dc, a.dc_stride, a.Wb, a.Hb, a.dc_mul, a.dc_smooth, a.kx_dc, a.kb_dc, bx, by, true,
              size_t(by) * a.dc_stride + bx, v);
-#pragma unroll
-    for (int c = 0; c < 3; ++c) s_gdc[c][ly][lx] = v[c];
+    s_gdc[ly][lx] = c == 0 ? v[0] : c == 1 ? v[1] : v[2];
   }
   __syncthreads();
   // cells: the ring's repeat its DC; each varblock's top-left block fills
@@ -864,58 +866,54 @@ __global__ __launch_bounds__(kPredThreads) void acpred_kernel(PredArgs a, int gr
   for (int i = tid; i < rw * rh; i += kPredThreads) {
     const int ly = i / rw, lx = i - ly * rw;
     const bool ring = lx == 0 || ly == 0 || lx == rw - 1 || ly == rh - 1;
-    int s = 0, cx = 1, cy = 1;
+    int cx = 1, cy = 1;
     if (!ring) {
       const uint32_t v = a.info[size_t(gy0 + ly - 1) * a.Wb + gx0 + lx - 1];
       if (v != kInvalid) {
         if (v & 0xF0u) continue;  // not the top-left block of its varblock
-        s = int(v & 15u);
+        const int s = int(v & 15u);
         if (s == 0 || (s >= 4 && s <= 11)) {
           cx = vb_bx(s);
           cy = vb_by(s);
         }
       }
     }
-    const int mx = cx == 4 ? 2 : cx - 1, my = cy == 4 ? 2 : cy - 1;
-#pragma unroll 1
-    for (int c = 0; c < 3; ++c) {
-      if (cx == 1 && cy == 1) {
-        const float d = s_gdc[c][ly][lx];
-        s_cell[c][2 * ly][2 * lx] = d;
-        s_cell[c][2 * ly][2 * lx + 1] = d;
-        s_cell[c][2 * ly + 1][2 * lx] = d;
-        s_cell[c][2 * ly + 1][2 * lx + 1] = d;
-        continue;
-      }
-      // columns first: t[j][ix] = sum_iy U_y[j][iy] D[iy][ix]
-      float t[8][4];
-#pragma unroll
-      for (int j = 0; j < 8; ++j)
-#pragma unroll
-        for (int ix = 0; ix < 4; ++ix) {
-          float acc = 0.0f;
-#pragma unroll
-          for (int iy = 0; iy < 4; ++iy)
-            if (iy < cy && ix < cx) acc = fmaf(s_u[my][j][iy], s_gdc[c][ly + iy][lx + ix], acc);
-          t[j][ix] = acc;
-        }
-      for (int j = 0; j < 2 * cy; ++j)
-        for (int k = 0; k < 2 * cx; ++k) {
-          float acc = 0.0f;
-#pragma unroll
-          for (int ix = 0; ix < 4; ++ix)
-            if (ix < cx) acc = fmaf(s_u[mx][k][ix], t[j][ix], acc);
-          s_cell[c][2 * ly + j][2 * lx + k] = acc;
-        }
+    if (cx == 1 && cy == 1) {
+      const float d = s_gdc[ly][lx];
+      s_cell[2 * ly][2 * lx] = d;
+      s_cell[2 * ly][2 * lx + 1] = d;
+      s_cell[2 * ly + 1][2 * lx] = d;
+      s_cell[2 * ly + 1][2 * lx + 1] = d;
+      continue;
     }
+    const int mx = cx == 4 ? 2 : cx - 1, my = cy == 4 ? 2 : cy - 1;
+    // columns first: t[j][ix] = sum_iy U_y[j][iy] D[iy][ix]
+    float t[8][4];
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+#pragma unroll
+      for (int ix = 0; ix < 4; ++ix) {
+        float acc = 0.0f;
+#pragma unroll
+        for (int iy = 0; iy < 4; ++iy)
+          if (iy < cy && ix < cx) acc = fmaf(s_u[my][j][iy], s_gdc[ly + iy][lx + ix], acc);
+        t[j][ix] = acc;
+      }
+    for (int j = 0; j < 2 * cy; ++j)
+      for (int k = 0; k < 2 * cx; ++k) {
+        float acc = 0.0f;
+#pragma unroll
+        for (int ix = 0; ix < 4; ++ix)
+          if (ix < cx) acc = fmaf(s_u[mx][k][ix], t[j][ix], acc);
+        s_cell[2 * ly + j][2 * lx + k] = acc;
+      }
   }
   __syncthreads();
-  // adaptive smoothing of the group's cells (not the ring's), per channel,
-  // from the unsmoothed neighbours
+  // adaptive smoothing of the group's cells (not the ring's) from the
+  // unsmoothed neighbours
   const int cw = 2 * gw, ncell = cw * 2 * gh;
   constexpr int kCellsPerThread = (2 * kGroupBlocks) * (2 * kGroupBlocks) / kPredThreads;
-#pragma unroll 1
-  for (int c = 0; c < 3; ++c) {
+  {
     const float q = a.dc_mul[c];
     float nv[kCellsPerThread];
 #pragma unroll
@@ -924,11 +922,11 @@ __global__ __launch_bounds__(kPredThreads) void acpred_kernel(PredArgs a, int gr
       nv[k] = 0.0f;
       if (i < ncell) {
         const int y = 2 + i / cw, x = 2 + i % cw;
-        const float sv = s_cell[c][y][x];
-        const float e = (s_cell[c][y - 1][x] + s_cell[c][y + 1][x]) + (s_cell[c][y][x - 1] + s_cell[c][y][x + 1]);
-        const float g = (s_cell[c][y - 1][x - 1] + s_cell[c][y - 1][x + 1]) +
-                        (s_cell[c][y + 1][x - 1] + s_cell[c][y + 1][x + 1]);
-        const float wa = fmaf(0.12f, sv, fmaf(0.2f, e, 0.02f * g));
+        const float sv = s_cell[y][x];
+        const float e = (s_cell[y - 1][x] + s_cell[y + 1][x]) + (s_cell[y][x - 1] + s_cell[y][x + 1]);
+        const float gd = (s_cell[y - 1][x - 1] + s_cell[y - 1][x + 1]) +
+                         (s_cell[y + 1][x - 1] + s_cell[y + 1][x + 1]);
+        const float wa = fmaf(0.12f, sv, fmaf(0.2f, e, 0.02f * gd));
         nv[k] = (sv - 1.7f * q <= wa && wa <= sv + 1.7f * q) ? wa : sv;
       }
     }
@@ -936,17 +934,15 @@ __global__ __launch_bounds__(kPredThreads) void acpred_kernel(PredArgs a, int gr
 #pragma unroll
     for (int k = 0; k < kCellsPerThread; ++k) {
       const int i = tid + kPredThreads * k;
-      if (i < ncell) s_cell[c][2 + i / cw][2 + i % cw] = nv[k];
+      if (i < ncell) s_cell[2 + i / cw][2 + i % cw] = nv[k];
     }
   }
   __syncthreads();
-  // per block and channel: its 2x2 share (2 dx + i, 2 dy + j) of the
-  // varblock's predicted coefficients from the varblock's cells S
-  // (DCT family: V_y S V_x^T; 8x8 types: the I.2.7.3 forms), the LLF
-  // corner set to 0
+  // per block: its 2x2 share (2 dx + i, 2 dy + j) of the varblock's
+  // predicted coefficients from the varblock's cells S (DCT family:
+  // V_y S V_x^T; 8x8 types: the I.2.7.3 forms), the LLF corner set to 0
   const size_t w2 = 2 * size_t(a.Wb);
-  for (int it = tid; it < 3 * gw * gh; it += kPredThreads) {
-    const int c = it / (gw * gh), b = it - c * (gw * gh);
+  for (int b = tid; b < gw * gh; b += kPredThreads) {
     const int ly = b / gw, lx = b - ly * gw;
     const uint32_t v = a.info[size_t(gy0 + ly) * a.Wb + gx0 + lx];
     float out[2][2] = {{0.0f, 0.0f}, {0.0f, 0.0f}};
@@ -965,14 +961,14 @@ __global__ __launch_bounds__(kPredThreads) void acpred_kernel(PredArgs a, int gr
             float acc = 0.0f;
             for (int r = 0; r < 2 * cy; ++r) {
               float row = 0.0f;
-              for (int k = 0; k < 2 * cx; ++k) row = fmaf(s_v[mx][x][k], s_cell[c][oy + r][ox + k], row);
+              for (int k = 0; k < 2 * cx; ++k) row = fmaf(s_v[mx][x][k], s_cell[oy + r][ox + k], row);
               acc = fmaf(s_v[my][y][r], row, acc);
             }
             out[j][i] = acc;
           }
       } else {
-        const float c00 = s_cell[c][oy][ox], c01 = s_cell[c][oy][ox + 1];
-        const float c10 = s_cell[c][oy + 1][ox], c11 = s_cell[c][oy + 1][ox + 1];
+        const float c00 = s_cell[oy][ox], c01 = s_cell[oy][ox + 1];
+        const float c10 = s_cell[oy + 1][ox], c11 = s_cell[oy + 1][ox + 1];
         if (s == 13) {  // DCT8x4: DC pair (0, 0), (1, 0)
           const float dc0 = 0.5f * (c00 + c10), ac0 = 0.5f * (c00 - c10);
           const float dc1 = 0.5f * (c01 + c11), ac1 = 0.5f * (c01 - c11);
@@ -2583,7 +2579,7 @@ jxlr_status jxlr_ac_prediction(jxlr_ctx* ctx, const jxlr_frame_params* p, const 
   const int gx = (Wb + kGroupBlocks - 1) / kGroupBlocks, gy = (Hb + kGroupBlocks - 1) / kGroupBlocks;
   DeviceGuard g(ctx->device);
   if (!g.ok) return JXLR_E_HIP;
-  hipLaunchKernelGGL(acpred_kernel, dim3(gx * gy), dim3(kPredThreads), 0, stream, a, gx);
+  hipLaunchKernelGGL(acpred_kernel, dim3(3 * gx * gy), dim3(kPredThreads), 0, stream, a, gx);
   return launch_status(hipGetLastError());
 }
 

@@ -44,11 +44,12 @@ EPF_DX = range(-4, 7)
 EPF_DY = range(-4, 5)
 
 
-def affected_mask(p, gpu_passes, orc_passes):
+def affected_mask(p, gpu_passes, orc_passes, start=None):
     """Pixels whose value may legitimately differ because an integer decision
-    differs.  gpu_passes / orc_passes: lists of (guide (3,H,W) u8, sigma (Hb,Wb))."""
+    differs.  gpu_passes / orc_passes: lists of (guide (3,H,W) u8, sigma (Hb,Wb));
+    start: pixels already affected before the first pass (or None)."""
     H, W = p.ysize, p.xsize
-    bad = np.zeros((H, W), bool)
+    bad = np.zeros((H, W), bool) if start is None else start.copy()
     stats = []
     for (gg, sg), (go, so) in zip(gpu_passes, orc_passes):
         gmis = np.any(gg != go, axis=0)
@@ -121,12 +122,36 @@ def spread_to_varblocks(mask, strategy):
     return np.kron(hit, np.ones((8, 8), bool))[:H, :W]
 
 
-def compare_rgb(p, gpu, orc, strategy=None):
+def acpred_mask(q, frame, rel=1e-5):
+    """AC prediction's smoothing test (|wa - s| <= 1.7 dcq) is taken in
+    binary32 on the GPU: the pixels of every varblock holding a cell whose
+    test is within rel of its boundary (relative to dcq and the cell's size),
+    from the oracle's margins.  q: oracle parameters."""
+    from oracle import oracle as O
+    Hb, Wb = frame["strategy"].shape
+    dq = frame["dc"].astype(np.float64) * np.array(q.dc_mul)[:, None, None]
+    dq /= (2.0 ** np.array(list(q.extra_levels)))[:, None, None]
+    if q.dc_smoothing:
+        dq = O.dc_smooth(q, dq)
+    dq[0] += q.kx_dc * dq[1]
+    dq[2] += q.kb_dc * dq[1]
+    cells, margin = O.ac_prediction_image(q, frame["strategy"], dq, want_margin=True)
+    tol = rel * (np.array(q.dc_mul)[:, None, None] + np.abs(cells))
+    near = (np.abs(margin) <= tol).any(axis=0)
+    blocks = near.reshape(Hb, 2, Wb, 2).any(axis=(1, 3))
+    ids = varblock_ids(frame["strategy"])
+    hit = np.isin(ids, np.unique(ids[blocks]))
+    return np.kron(hit, np.ones((8, 8), bool))[:q.ysize, :q.xsize], int(near.sum())
+
+
+def compare_rgb(p, gpu, orc, strategy=None, start=None):
     """Max-abs error of the final [0,1]-scaled RGB outside flip-affected
     pixels, plus the flip statistics.  With the quantization constraint on,
-    pass the DctSelect map: the mask spreads over whole varblocks."""
+    pass the DctSelect map: the mask spreads over whole varblocks.  start:
+    pixels affected before the filters (AC prediction's near-boundary
+    varblocks)."""
     mask, stats = affected_mask(p, [(g, s) for _, g, s in gpu["epf"]],
-                                [(g, s) for _, g, s in orc["epf"]])
+                                [(g, s) for _, g, s in orc["epf"]], start)
     if p.qco and p.epf_iters > 0:
         mask = spread_to_varblocks(mask, strategy)
     if p.gab:

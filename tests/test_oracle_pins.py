@@ -689,10 +689,14 @@ def test_ac_prediction_image_brute_force():
     q = (0.5, 1.0, 2.0)
     p = O.params(8 * Wb, 8 * Hb, dc_mul=q, ac_prediction=1)
     d = np.stack([rng.integers(-3, 4, size=(Hb, Wb)) * qq for qq in q]).astype(np.float64)
-    got = O.ac_prediction_image(p, strat, d)
+    got, margin = O.ac_prediction_image(p, strat, d, want_margin=True)
+    k = np.array([[0.02, 0.2, 0.02], [0.2, 0.12, 0.2], [0.02, 0.2, 0.02]])
     for c in range(3):
         want = _brute_cells(d[c], q[c])
         np.testing.assert_allclose(got[c], want, atol=1e-12)
+        img = np.kron(np.pad(d[c], 1, mode="symmetric"), np.ones((2, 2)))
+        wa = ndi.correlate(img, k, mode="nearest")
+        np.testing.assert_allclose(margin[c], (np.abs(wa - img) - 1.7 * q[c])[2:-2, 2:-2], atol=1e-12)
         assert np.abs(want - np.kron(d[c], np.ones((2, 2)))).max() > 0.1  # smoothing acted
 
 
