@@ -76,6 +76,7 @@ void orc_params_default(orc_params* p, int32_t xsize, int32_t ysize) {
   p->qco = 0;                 /* C.10: qco defaults to false */
   p->qco_interval_mul = 0.5;
   p->ac_prediction = 0;
+  p->noise = 0;  /* kNoise clear; the LUT is read only when it is set (C.4.8) */
 }
 
 int orc_num_threads(void) {
@@ -1506,6 +1507,120 @@ int orc_qco(const orc_params* p, const uint8_t* strategy, const uint8_t* qf_minu
 }
 
 /* ======================================================================= */
+/* Noise (K.5)                                                             */
+/* ======================================================================= */
+
+/* K.5.2: the draft's SplitMix64 mixing function of a 64-bit state. */
+uint64_t orc_splitmix64(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  z ^= z >> 31;
+  return z;
+}
+
+/* K.5.2: the three pseudorandom channels RR, RG, RB of the group whose
+ * top-left pixel is (x0, y0), gw x gh samples each: eight XorShift128+
+ * generators seeded from (y0 << 32) + x0 through SplitMix64; per row and per
+ * segment of up to 16 samples one step of all eight gives sixteen 32-bit
+ * words, sample j of the segment being the binary32 with exponent 0 and the
+ * top 23 bits of word j as mantissa, minus 1.  Channels, rows and segments
+ * follow in that order from one generator state.  Reading: the printed step
+ * updates s1 only; a XorShift128+ step also moves the old second word into
+ * the first place, so after it s1 takes the old s0 and s0 the updated value
+ * (without the exchange s0 would never change).  out: [3][gh][gw]. */
+void orc_noise_channels(int32_t gw, int32_t gh, int32_t x0, int32_t y0, float* out) {
+  uint64_t s0[8], s1[8];
+  const uint64_t seed = ((uint64_t)(uint32_t)y0 << 32) + (uint64_t)(uint32_t)x0;
+  s0[0] = orc_splitmix64(seed + 0x9E3779B97F4A7C15ull);
+  s1[0] = orc_splitmix64(s0[0]);
+  for (int i = 1; i < 8; ++i) {
+    s0[i] = orc_splitmix64(s1[i - 1]);
+    s1[i] = orc_splitmix64(s0[i]);
+  }
+  for (int c = 0; c < 3; ++c)
+    for (int32_t y = 0; y < gh; ++y)
+      for (int32_t x = 0; x < gw; x += 16) {
+        uint32_t bits[16];
+        for (int i = 0; i < 8; ++i) {
+          /* one XorShift128+ step of generator i, as printed, then the two
+           * state words change places (s1 the first word, s0 the second) */
+          const uint64_t t = s0[i];
+          s1[i] ^= s1[i] << 23;
+          const uint64_t b = s1[i] + s0[i];
+          s1[i] ^= s0[i] ^ (s1[i] >> 18) ^ (s0[i] >> 5);
+          s0[i] = s1[i];
+          s1[i] = t;
+          bits[2 * i] = (uint32_t)b;
+          bits[2 * i + 1] = (uint32_t)(b >> 32);
+        }
+        for (int j = 0; j < 16 && x + j < gw; ++j) {
+          const uint32_t u = (bits[j] >> 9) | 0x3F800000u;
+          float f;
+          memcpy(&f, &u, sizeof(f));
+          out[((size_t)c * gh + y) * gw + x + j] = f - 1.0f;
+        }
+      }
+}
+
+/* K.5: noise over a cropped XYB frame (after Gaborish), per group of 256 x 256
+ * pixels (6.2): the three channels of K.5.2, each convolved with the 5x5
+ * kernel of 1 at distance 2 up, down, left and right and -4 at the centre
+ * (6.5 mirroring at the group's size), times 0.22, give A_R, A_G, A_B; the
+ * strengths S_R, S_G from the LUT at 14 (Y + X) and 14 (Y - X) (integer part
+ * clamped to [0, 14], linear interpolation with the fractional part, result
+ * clamped to [0, 1]); N_R = (0.01 A_R + 0.99 A_B) S_R and
+ * N_G = (0.01 A_G + 0.99 A_B) S_G are added: X += N_R - N_G,
+ * Y += N_R + N_G, B += 0.935669 (N_R + N_G).  Readings: the channels are
+ * generated at the group's size, and the 5x5 kernel mirrors at the group's
+ * edges; the fractional part is taken before the integer part is clamped. */
+int orc_noise(const orc_params* p, const double* in, double* out) {
+  int st = check_params(p);
+  if (st) return st;
+  const int32_t W = p->xsize, H = p->ysize;
+  const size_t plane = (size_t)W * H;
+  memcpy(out, in, sizeof(double) * 3 * plane);
+  float* ch = (float*)malloc(sizeof(float) * 3 * 256 * 256);
+  if (!ch) return ORC_E_SIZE;
+  for (int32_t y0 = 0; y0 < H; y0 += 256)
+    for (int32_t x0 = 0; x0 < W; x0 += 256) {
+      const int32_t gw = W - x0 < 256 ? W - x0 : 256, gh = H - y0 < 256 ? H - y0 : 256;
+      orc_noise_channels(gw, gh, x0, y0, ch);
+      for (int32_t y = 0; y < gh; ++y)
+        for (int32_t x = 0; x < gw; ++x) {
+          double A[3];
+          for (int c = 0; c < 3; ++c) {
+            const float* r = ch + (size_t)c * gh * gw;
+#define R_AT(yy, xx) ((double)r[(size_t)mirror((yy), gh) * gw + mirror((xx), gw)])
+            A[c] = 0.22 * (R_AT(y - 2, x) + R_AT(y, x - 2) + R_AT(y, x + 2) + R_AT(y + 2, x) -
+                           4.0 * R_AT(y, x));
+#undef R_AT
+          }
+          const size_t i = (size_t)(y0 + y) * W + x0 + x;
+          const double X = in[i], Y = in[plane + i];
+          double S[2];
+          const double inp[2] = {Y + X, Y - X};
+          for (int k = 0; k < 2; ++k) {
+            const double sc = inp[k] * 14.0;
+            double in_int = floor(sc);
+            const double in_frac = sc - in_int;
+            if (in_int < 0.0) in_int = 0.0;
+            if (in_int > 14.0) in_int = 14.0;
+            const int ii = (int)in_int;
+            double v = p->noise_lut[ii] * (1.0 - in_frac) + p->noise_lut[ii + 1] * in_frac;
+            S[k] = v < 0.0 ? 0.0 : v > 1.0 ? 1.0 : v;
+          }
+          const double NR = 0.01 * A[0] * S[0] + 0.99 * A[2] * S[0];
+          const double NG = 0.01 * A[1] * S[1] + 0.99 * A[2] * S[1];
+          out[i] = X + NR - NG;
+          out[plane + i] = Y + NR + NG;
+          out[2 * plane + i] = in[2 * plane + i] + 0.935669 * (NR + NG);
+        }
+    }
+  free(ch);
+  return ORC_OK;
+}
+
+/* ======================================================================= */
 /* Gaborish (J.4)                                                          */
 /* ======================================================================= */
 
@@ -1612,6 +1727,11 @@ int orc_decode(const orc_params* p, const int32_t* const ac[3], const int32_t* c
   free(r);
   if (!st && p->gab) {
     st = orc_gaborish(p, a, b);
+    double* t = a; a = b; b = t;
+  }
+  /* K.1: noise after Gaborish */
+  if (!st && p->noise) {
+    st = orc_noise(p, a, b);
     double* t = a; a = b; b = t;
   }
   if (!st) st = orc_xyb_to_rgb(p, a, rgb);

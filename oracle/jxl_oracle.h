@@ -75,6 +75,8 @@ typedef struct {
   int32_t qco;                 /* loop_filter.qco (C.10): J.3 after the EPF passes */
   double  qco_interval_mul;    /* loop_filter.qco_interval_mul (C.10) */
   int32_t ac_prediction;       /* Annex H (kSkipPredictLF clear); 0 = skipped */
+  int32_t noise;               /* kNoise (K.5); 0 = skipped */
+  double  noise_lut[16];       /* C.4.8 LUT, each u(10) / 1024 */
 } orc_params;
 
 /* Fills the defaults the draft gives for every field (C.4, C.10, L.2, A.4.5). */
@@ -146,6 +148,12 @@ int orc_epf_pass(const orc_params* p, const uint8_t* strategy,
  * (all [3][ysize][xsize]; out may not alias orig). */
 int orc_qco(const orc_params* p, const uint8_t* strategy, const uint8_t* qf_minus_1,
             const double* orig, const double* filt, double* out);
+/* K.5.2 SplitMix64 and the three pseudorandom channels [3][gh][gw] of the
+ * group with top-left pixel (x0, y0). */
+uint64_t orc_splitmix64(uint64_t z);
+void orc_noise_channels(int32_t gw, int32_t gh, int32_t x0, int32_t y0, float* out);
+/* K.5 noise over a cropped XYB frame (applied after Gaborish). */
+int orc_noise(const orc_params* p, const double* in, double* out);
 /* Gaborish (J.4). */
 int orc_gaborish(const orc_params* p, const double* in, double* out);
 
@@ -157,7 +165,8 @@ int orc_quantize_srgb(int32_t bits, int64_t n, const double* lin, uint16_t* out)
 
 /* ---- whole path -------------------------------------------------------- */
 /* Reconstruct, epf_iters EPF passes, the quantization constraint (if p->qco
- * and at least one pass), Gaborish (if p->gab), XYB -> RGB.
+ * and at least one pass), Gaborish (if p->gab), noise (if p->noise),
+ * XYB -> RGB.
  * rgb: [3][ysize][xsize] of [0,1]-scaled linear RGB. */
 int orc_decode(const orc_params* p,
                const int32_t* const ac[3], const int32_t* const dc[3],

@@ -38,6 +38,8 @@ class OrcParams(C.Structure):
         ("qco", C.c_int32),
         ("qco_interval_mul", C.c_double),
         ("ac_prediction", C.c_int32),
+        ("noise", C.c_int32),
+        ("noise_lut", C.c_double * 16),
     ]
 
 
@@ -83,6 +85,10 @@ def lib():
         L.orc_epf_pass.argtypes = [P, _u8p, _u8p, _u8p, _f64p, _f64p, C.c_void_p, C.c_void_p]
         L.orc_qco.argtypes = [P, _u8p, _u8p, _f64p, _f64p, _f64p]
         L.orc_gaborish.argtypes = [P, _f64p, _f64p]
+        L.orc_splitmix64.argtypes = [C.c_uint64]
+        L.orc_splitmix64.restype = C.c_uint64
+        L.orc_noise_channels.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.c_int32, _f32p]
+        L.orc_noise.argtypes = [P, _f64p, _f64p]
         L.orc_xyb_to_rgb.argtypes = [P, _f64p, _f64p]
         L.orc_quantize_srgb.argtypes = [C.c_int32, C.c_int64, _f64p, _u16p]
         L.orc_decode.argtypes = [P, ptr3, ptr3, _u8p, _u8p, _u8p, _f32p, _f32p, _f64p]
@@ -312,6 +318,25 @@ def qco(p, frame, orig, filt):
     return out
 
 
+def splitmix64(z):
+    return lib().orc_splitmix64(int(z) & (2**64 - 1))
+
+
+def noise_channels(gw, gh, x0, y0):
+    """K.5.2 pseudorandom channels (3, gh, gw), binary32."""
+    out = np.zeros((3, gh, gw), np.float32)
+    lib().orc_noise_channels(gw, gh, x0, y0, out)
+    return out
+
+
+def noise(p, xyb):
+    """K.5 noise over a cropped XYB frame."""
+    xyb = np.ascontiguousarray(xyb, dtype=np.float64)
+    out = np.zeros_like(xyb)
+    _check(lib().orc_noise(C.byref(p), xyb, out))
+    return out
+
+
 def gaborish(p, xyb):
     xyb = np.ascontiguousarray(xyb, dtype=np.float64)
     out = np.zeros_like(xyb)
@@ -350,7 +375,7 @@ def decode(p, frame):
 def decode_stages(p, frame):
     """Whole path with every intermediate kept (for stage-by-stage comparison).
     Returns dict: recon, epf (list of (out, guide, sigma)), qco (when
-    applied), gab, rgb."""
+    applied), gab, noise (when applied), rgb."""
     res = {"recon": reconstruct(p, frame), "epf": []}
     cur = res["recon"]
     for _ in range(p.epf_iters):
@@ -363,6 +388,9 @@ def decode_stages(p, frame):
     if p.gab:
         cur = gaborish(p, cur)
     res["gab"] = cur
+    if p.noise:
+        cur = noise(p, cur)
+        res["noise"] = cur
     res["rgb"] = xyb_to_rgb(p, cur)
     return res
 

@@ -906,6 +906,115 @@ def test_qco_follows_the_filter_passes_in_decode():
 
 
 # --------------------------------------------------------------------------
+# Noise (K.5)
+# --------------------------------------------------------------------------
+
+M64 = 2 ** 64 - 1
+
+
+def _unxorshift_right(y, k):
+    # inverse of y = x ^ (x >> k) on 64 bits
+    x = y
+    for _ in range(64 // k + 1):
+        x = y ^ (x >> k)
+    return x & M64
+
+
+def test_splitmix64_inverts():
+    # the mixing function is a bijection; its inverse, written from the
+    # printed constants (modular inverses of the odd multipliers, inverse
+    # xor-shifts), undoes the oracle's value for random states
+    inv1 = pow(0xBF58476D1CE4E5B9, -1, 2 ** 64)
+    inv2 = pow(0x94D049BB133111EB, -1, 2 ** 64)
+    rng = _rng(100)
+    for z in [0, 1, M64] + [int(v) for v in rng.integers(0, 2 ** 63, size=50, dtype=np.int64)]:
+        y = O.splitmix64(z)
+        x = _unxorshift_right(y, 31)
+        x = (x * inv2) & M64
+        x = _unxorshift_right(x, 27)
+        x = (x * inv1) & M64
+        x = _unxorshift_right(x, 30)
+        assert x == z
+
+
+def test_noise_channels_are_uniform_23_bit_samples():
+    ch = O.noise_channels(256, 256, 0, 0)
+    assert ch.dtype == np.float32 and ch.min() >= 0.0 and ch.max() < 1.0
+    m = (ch.astype(np.float64) * 2 ** 23)
+    np.testing.assert_array_equal(m, np.round(m))  # exactly 23 mantissa bits
+    assert np.abs(ch.mean(axis=(1, 2)) - 0.5).max() < 0.005
+    assert np.abs(ch.var(axis=(1, 2)) - 1 / 12).max() < 0.002
+    bits = m.astype(np.int64)
+    for b in range(23):
+        assert abs(((bits >> b) & 1).mean() - 0.5) < 0.01, b
+    # neighbouring samples (different generators or steps) are uncorrelated
+    c = ch[0].astype(np.float64) - 0.5
+    assert abs((c[:, 1:] * c[:, :-1]).mean()) < 0.002
+    assert abs((c[1:, :] * c[:-1, :]).mean()) < 0.002
+    # deterministic per group and reseeded per group; a narrower group starts
+    # with the same first segment, then its rows take fewer steps
+    np.testing.assert_array_equal(O.noise_channels(256, 256, 0, 0), ch)
+    other = O.noise_channels(256, 256, 256, 0)
+    assert np.abs(other - ch).mean() > 0.2
+    small = O.noise_channels(16, 4, 0, 0)
+    np.testing.assert_array_equal(small[0, 0], ch[0, 0, :16])
+    assert np.abs(small[0, 1] - ch[0, 1, :16]).max() > 0.1
+
+
+def _noise_A(gw, gh, x0, y0):
+    ch = O.noise_channels(gw, gh, x0, y0).astype(np.float64)
+    k = np.zeros((5, 5))
+    k[0, 2] = k[4, 2] = k[2, 0] = k[2, 4] = 1.0
+    k[2, 2] = -4.0
+    return 0.22 * np.stack([ndi.correlate(c, k, mode="reflect") for c in ch])
+
+
+def test_noise_adds_lut_modulated_laplacian_of_the_channels():
+    # two groups (288 x 40): LUT = k / 16, inputs spanning below 0, the LUT
+    # range and above 15/14 so that the clamps act
+    W, H = 288, 40
+    lut = np.arange(16) / 16.0
+    p = O.params(W, H, noise=1, noise_lut=lut)
+    rng = _rng(101)
+    xyb = np.stack([rng.uniform(-0.1, 0.1, size=(H, W)), rng.uniform(-0.2, 1.3, size=(H, W)),
+                    rng.uniform(0.0, 1.0, size=(H, W))])
+    out = O.noise(p, xyb)
+    A = np.zeros((3, H, W))
+    A[:, :, :256] = _noise_A(256, H, 0, 0)
+    A[:, :, 256:] = _noise_A(32, H, 256, 0)
+
+    def strength(v):
+        sc = 14.0 * v
+        f = sc - np.floor(sc)
+        i = np.clip(np.floor(sc), 0, 14).astype(int)
+        return np.clip(lut[i] * (1 - f) + lut[i + 1] * f, 0.0, 1.0)
+
+    SR, SG = strength(xyb[1] + xyb[0]), strength(xyb[1] - xyb[0])
+    NR = (0.01 * A[0] + 0.99 * A[2]) * SR
+    NG = (0.01 * A[1] + 0.99 * A[2]) * SG
+    np.testing.assert_allclose(out[0] - xyb[0], NR - NG, atol=1e-12)
+    np.testing.assert_allclose(out[1] - xyb[1], NR + NG, atol=1e-12)
+    np.testing.assert_allclose(out[2] - xyb[2], 0.935669 * (NR + NG), atol=1e-12)
+    inR = xyb[1] + xyb[0]
+    assert np.abs(A).std() > 0.1 and (inR < 0).any() and (14 * inR >= 15).any()
+    # a zero LUT adds nothing
+    np.testing.assert_array_equal(O.noise(O.params(W, H, noise=1), xyb), xyb)
+
+
+def test_noise_follows_gaborish_in_decode():
+    W, H = 40, 24
+    f = _frame_of(0, W, H, _rng(102).integers(-200, 200, size=(3, 3, 5)),
+                  ac=_rng(103).integers(-4, 5, size=(3, 24, 40)).astype(np.int32))
+    kw = dict(dc_mul=(0.004, 0.004, 0.004), epf_iters=1, noise=1,
+              noise_lut=np.linspace(0.2, 0.8, 16))
+    p = O.params(W, H, **kw)
+    st = O.decode_stages(p, f)
+    np.testing.assert_array_equal(st["noise"], O.noise(p, st["gab"]))
+    np.testing.assert_allclose(O.decode(p, f), O.xyb_to_rgb(p, st["noise"]), atol=1e-12)
+    assert np.abs(st["noise"] - st["gab"]).max() > 1e-3
+
+
+# --------------------------------------------------------------------------
 # Gaborish (J.4)
 # --------------------------------------------------------------------------
 
