@@ -129,6 +129,14 @@ typedef struct {
    * jxlr_ac_prediction); jxlr_decode manages it.  The batch functions reject
    * it (JXLR_E_PARAM). */
   int32_t  ac_prediction;
+  /* Noise of K.5 (1; kNoise) or not (0, the default), after Gaborish: per
+   * 256x256 group three pseudorandom channels (K.5.2; SplitMix64-seeded
+   * XorShift128+, made by jxlr_noise_channels), their 5x5 Laplacian times
+   * 0.22, modulated by the strengths the LUT gives at 14 (Y + X) and
+   * 14 (Y - X).  Needs io->noise_raw for jxlr_finish; jxlr_decode manages it.
+   * The batch functions reject it (JXLR_E_PARAM). */
+  int32_t  noise;
+  float    noise_lut[16];     /* C.4.8: u(10) / 1024 each; finite */
 } jxlr_frame_params;
 
 /* Input and output planes of one frame.  With Wb = ceil(xsize/8),
@@ -167,6 +175,10 @@ typedef struct {
    * jxlr_ac_prediction and read by jxlr_reconstruct when p->ac_prediction;
    * may be NULL otherwise. */
   const float* ac_pred;
+  /* K.5 pseudorandom channels, float [3][ysize][xsize] (row stride xsize),
+   * written by jxlr_noise_channels and read by jxlr_finish when p->noise;
+   * may be NULL otherwise. */
+  const float* noise_raw;
 } jxlr_frame_io;
 
 typedef struct jxlr_ctx jxlr_ctx;
@@ -253,8 +265,14 @@ jxlr_status jxlr_qco_pass(jxlr_ctx* ctx, const jxlr_frame_params* p, const jxlr_
                           const uint8_t* info, const float* xyb_orig, float* xyb_io,
                           size_t xyb_stride, hipStream_t stream);
 
-/* Gaborish (J.4, when p->gab) and XYB -> RGB (L.2) into io->out in
- * p->out_format. */
+/* K.5.2: the three pseudorandom channels of every 256x256 group of the frame
+ * (frame-sized planes, float [3][ysize][xsize], row stride xsize, device
+ * memory owned by the caller); they depend on the frame size only. */
+jxlr_status jxlr_noise_channels(jxlr_ctx* ctx, const jxlr_frame_params* p, float* raw,
+                                hipStream_t stream);
+
+/* Gaborish (J.4, when p->gab), noise (K.5, when p->noise, from
+ * io->noise_raw) and XYB -> RGB (L.2) into io->out in p->out_format. */
 jxlr_status jxlr_finish(jxlr_ctx* ctx, const jxlr_frame_params* p, const jxlr_frame_io* io,
                         const float* xyb, size_t xyb_stride, hipStream_t stream);
 

@@ -1778,6 +1778,9 @@ struct FinishArgs {
   size_t out_stride;
   const float* thr;  // decision thresholds of the 8- or 16-bit code
   const uint8_t* start8;  // 8-bit code of each binary32 bucket
+  int noise;                  // K.5 after Gaborish
+  const float* noise_raw;     // the pseudorandom channels [3][H][W] (row stride W)
+  float noise_lut[16];
 };
 
 // sRGB transfer function of the clamped value, as an estimate: the power
@@ -1837,6 +1840,44 @@ __device__ inline typename OutT<FMT>::T encode_out(float v, const float* __restr
   else return uint16_t(srgb_code(v, thr, 65535));
 }
 
+// K.5.3 on one pixel (column x, row y; v: X, Y, B after Gaborish): the
+// 5x5 Laplacian of the three pseudorandom channels at the pixel, mirrored
+// at the edges of its 256x256 group, times 0.22, modulated by the LUT
+// strengths of Y + X and Y - X (lut: 16 entries).
+__device__ inline void noise_add(const FinishArgs& a, int x, int y, float (&v)[3],
+                                 const float* __restrict__ lut) {
+  const int x0 = x & ~255, y0 = y & ~255;
+  const int gw = min(256, a.W - x0), gh = min(256, a.H - y0);
+  const int lx = x - x0, ly = y - y0;
+  const size_t W = size_t(a.W), plane = size_t(a.H) * W;
+  const size_t c0 = size_t(y) * W + x;
+  const size_t up = size_t(y0 + mirror(ly - 2, gh)) * W + x;
+  const size_t dn = size_t(y0 + mirror(ly + 2, gh)) * W + x;
+  const size_t lf = size_t(y) * W + x0 + mirror(lx - 2, gw);
+  const size_t rt = size_t(y) * W + x0 + mirror(lx + 2, gw);
+  float A[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const float* r = a.noise_raw + c * plane;
+    A[c] = 0.22f * ((r[up] + r[lf]) + (r[rt] + r[dn]) - 4.0f * r[c0]);
+  }
+  const float in[2] = {v[1] + v[0], v[1] - v[0]};
+  float S[2];
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const float sc = in[k] * 14.0f;
+    const float fl = floorf(sc);
+    const float fr = sc - fl;
+    const int ii = int(fminf(fmaxf(fl, 0.0f), 14.0f));
+    S[k] = fminf(fmaxf(fmaf(lut[ii + 1], fr, lut[ii] * (1.0f - fr)), 0.0f), 1.0f);
+  }
+  const float nr = fmaf(0.01f * A[0], S[0], 0.99f * A[2] * S[0]);
+  const float ng = fmaf(0.01f * A[1], S[1], 0.99f * A[2] * S[1]);
+  v[0] += nr - ng;
+  v[1] += nr + ng;
+  v[2] = fmaf(0.935669f, nr + ng, v[2]);
+}
+
 // Output rows per finish thread (ROWS); a 64x32 tile takes 64 * 32 / ROWS
 // threads.  The single-frame kernel uses 4 rows, the batch kernel 8 (fewer
 // re-read halo rows, measured faster over many small frames).
@@ -1851,17 +1892,20 @@ constexpr int fin_threads() { return 64 * 32 / ROWS; }
 // at offsets -1 and +1.  The input and output planes are distinct buffers;
 // saying so lets the compiler issue the loads of later rows ahead of earlier
 // stores.
-template <int ROWS, int FMT, bool EDGE>
+template <int ROWS, int FMT, bool EDGE, bool NOISE = false>
 __device__ inline void finish_strip(const FinishArgs& a, const float* __restrict__ in,
                                     void* __restrict__ o0, void* __restrict__ o1,
                                     void* __restrict__ o2, const float* __restrict__ thr,
-                                    const uint8_t* __restrict__ start8, int x, int ys, int nrows) {
+                                    const uint8_t* __restrict__ start8, int x, int ys, int nrows,
+                                    const float* __restrict__ lut = nullptr) {
   using T = typename OutT<FMT>::T;
   const size_t plane = size_t(a.H) * a.stride;
   T* out[3] = {static_cast<T*>(o0) + size_t(ys) * a.out_stride + x,
                static_cast<T*>(o1) + size_t(ys) * a.out_stride + x,
                static_cast<T*>(o2) + size_t(ys) * a.out_stride + x};
-  auto store = [&](int r, const float (&v)[3]) {
+  auto store = [&](int r, const float (&vin)[3]) {
+    float v[3] = {vin[0], vin[1], vin[2]};
+    if constexpr (NOISE) noise_add(a, x, ys + r, v, lut);
     float rgb[3];
     xyb_to_rgb(a, v, rgb);
 #pragma unroll
@@ -1932,12 +1976,19 @@ __device__ inline void finish_strip(const FinishArgs& a, const float* __restrict
 // load per channel and neighbour column.  Only tiles that touch the frame
 // edge take the mirrored indexing.  The 8-bit code tables are staged in
 // LDS; the 16-bit thresholds (256 KB) are read through the cache.
-template <int ROWS>
+template <int ROWS, bool NOISE = false>
 __device__ __attribute__((always_inline)) inline void finish_tile(const FinishArgs& a, int tbx, int tby) {
   __shared__ float s_thr[257];
   __shared__ uint32_t s_start[kSrgbBucketsPadded / 4];
+  __shared__ float s_lut[16];
   const int tid = threadIdx.x;
   const int x0 = 64 * tbx, y0 = 32 * tby;
+  if constexpr (NOISE) {
+    if (tid == 0)
+#pragma unroll
+      for (int i = 0; i < 16; ++i) s_lut[i] = a.noise_lut[i];
+    __syncthreads();
+  }
   if (a.format == JXLR_OUT_U8_SRGB) {
     for (int i = tid; i < 257; i += fin_threads<ROWS>()) s_thr[i] = a.thr[i];
     for (int i = tid; i < kSrgbBucketsPadded / 4; i += fin_threads<ROWS>())
@@ -1950,10 +2001,14 @@ __device__ __attribute__((always_inline)) inline void finish_tile(const FinishAr
   const int nrows = min(ROWS, a.H - ys);
   const uint8_t* start8 = reinterpret_cast<const uint8_t*>(s_start);
 #define JXLR_FINISH(FMT, THR, ST)                                                                 \
-  (edge ? finish_strip<ROWS, FMT, true>(a, a.in, a.out[0], a.out[1], a.out[2], THR, ST, x, ys,    \
-                                        nrows)                                                   \
-        : finish_strip<ROWS, FMT, false>(a, a.in, a.out[0], a.out[1], a.out[2], THR, ST, x, ys,   \
-                                         nrows))
+  (NOISE ? (edge ? finish_strip<ROWS, FMT, true, true>(a, a.in, a.out[0], a.out[1], a.out[2],    \
+                                                         THR, ST, x, ys, nrows, s_lut)           \
+                   : finish_strip<ROWS, FMT, false, true>(a, a.in, a.out[0], a.out[1], a.out[2],   \
+                                                          THR, ST, x, ys, nrows, s_lut))         \
+   : edge ? finish_strip<ROWS, FMT, true>(a, a.in, a.out[0], a.out[1], a.out[2], THR, ST, x, ys,  \
+                                          nrows)                                                 \
+          : finish_strip<ROWS, FMT, false>(a, a.in, a.out[0], a.out[1], a.out[2], THR, ST, x, ys, \
+                                           nrows))
   if (a.format == JXLR_OUT_F32)
     JXLR_FINISH(JXLR_OUT_F32, nullptr, nullptr);
   else if (a.format == JXLR_OUT_U8_SRGB)
@@ -1961,6 +2016,80 @@ __device__ __attribute__((always_inline)) inline void finish_tile(const FinishAr
   else
     JXLR_FINISH(JXLR_OUT_U16_SRGB, a.thr, nullptr);
 #undef JXLR_FINISH
+}
+
+// ---------------------------------------------------------------------------
+// Noise channels (K.5.2).  One workgroup per 256x256 group and channel; each
+// thread runs one of the eight generators over 16 rows: it seeds the
+// generator (SplitMix64 chain), jumps it ahead to its first step with the
+// tables' powers of the generator's GF(2)-linear step map, then writes the
+// two samples per 16-sample segment that its 64-bit outputs give.
+
+struct NoiseArgs {
+  int W, H;
+  float* raw;  // [3][H][W]
+  const DeviceTables* __restrict__ tab;
+};
+
+constexpr int kNoiseRows = 16;
+constexpr int kNoiseThreads = 8 * (256 / kNoiseRows);
+
+__device__ inline uint64_t splitmix64(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+__global__ __launch_bounds__(kNoiseThreads) void noise_kernel(NoiseArgs a, int groups_x) {
+  const int c = blockIdx.x % 3, g = blockIdx.x / 3;
+  const int x0 = 256 * (g % groups_x), y0 = 256 * (g / groups_x);
+  const int gw = min(256, a.W - x0), gh = min(256, a.H - y0);
+  const int lane = threadIdx.x & 7, r0 = kNoiseRows * (threadIdx.x >> 3);
+  if (r0 >= gh) return;
+  const int nseg = (gw + 15) / 16;
+  // generator `lane`: first word s1, second word s0 of the seeding chain
+  const uint64_t seed = (uint64_t(uint32_t(y0)) << 32) + uint64_t(uint32_t(x0));
+  uint64_t s0 = splitmix64(seed + 0x9E3779B97F4A7C15ull);
+  uint64_t s1 = splitmix64(s0);
+  for (int i = 1; i <= lane; ++i) {
+    s0 = splitmix64(s1);
+    s1 = splitmix64(s0);
+  }
+  uint64_t A = s1, B = s0;
+  // jump to step (c gh + r0) nseg: the 2^k-th power of the step map for each
+  // set bit k
+  const uint32_t t0 = uint32_t((c * gh + r0) * nseg);
+  const DeviceTables* __restrict__ T = a.tab;
+  for (int k = 0; k < 14; ++k) {
+    if (!((t0 >> k) & 1u)) continue;
+    uint64_t na = 0, nb = 0;
+#pragma unroll 8
+    for (int r = 0; r < 64; ++r) {
+      const uint32_t pa = uint32_t(__popcll(T->noise_jump[k][r][0] & A) +
+                                   __popcll(T->noise_jump[k][r][1] & B)) & 1u;
+      const uint32_t pb = uint32_t(__popcll(T->noise_jump[k][64 + r][0] & A) +
+                                   __popcll(T->noise_jump[k][64 + r][1] & B)) & 1u;
+      na |= uint64_t(pa) << r;
+      nb |= uint64_t(pb) << r;
+    }
+    A = na;
+    B = nb;
+  }
+  const int r1 = min(r0 + kNoiseRows, gh);
+  for (int r = r0; r < r1; ++r) {
+    float* row = a.raw + (size_t(c) * a.H + y0 + r) * a.W + x0;
+    for (int sg = 0; sg < nseg; ++sg) {
+      const uint64_t u = A ^ (A << 23);
+      const uint64_t out = u + B;
+      const uint64_t nb = u ^ B ^ (u >> 18) ^ (B >> 5);
+      A = B;
+      B = nb;
+      const int x = 16 * sg + 2 * lane;
+      // binary32 with exponent 0 and the top 23 bits as mantissa, minus 1
+      if (x < gw) row[x] = __uint_as_float((uint32_t(out) >> 9) | 0x3F800000u) - 1.0f;
+      if (x + 1 < gw) row[x + 1] = __uint_as_float((uint32_t(out >> 32) >> 9) | 0x3F800000u) - 1.0f;
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -2001,10 +2130,11 @@ __global__ __launch_bounds__(kEpfThreads, kEpfMinBlocks) void epf_kernel(EpfArgs
   const int t = xcd_tile(blockIdx.x, gridDim.x);
   epf_tile(a, t % tiles_x, t / tiles_x);
 }
+template <bool NOISE>
 __global__ __launch_bounds__(fin_threads<kFinRowsFrame>()) void finish_kernel(FinishArgs a,
                                                                               int tiles_x) {
   const int t = xcd_tile(blockIdx.x, gridDim.x);
-  finish_tile<kFinRowsFrame>(a, t % tiles_x, t / tiles_x);
+  finish_tile<kFinRowsFrame, NOISE>(a, t % tiles_x, t / tiles_x);
 }
 
 // The batch kernels share one tile list over reconstruction, EPF and finish.
@@ -2172,6 +2302,9 @@ jxlr_status check_params(const jxlr_frame_params* p) {
   if (p->qco < 0 || p->qco > 1) return JXLR_E_PARAM;
   if (p->ac_prediction < 0 || p->ac_prediction > 1 || (p->ac_prediction && !el0))
     return JXLR_E_PARAM;
+  if (p->noise < 0 || p->noise > 1) return JXLR_E_PARAM;
+  for (int i = 0; i < 16; ++i)
+    if (!std::isfinite(p->noise_lut[i])) return JXLR_E_PARAM;
   if (p->qco && (!el0 || !(p->qco_interval_mul >= 0.0f) || !std::isfinite(p->qco_interval_mul)))
     return JXLR_E_PARAM;
   return JXLR_OK;
@@ -2238,6 +2371,7 @@ jxlr_status jxlr_params_default(jxlr_frame_params* p, uint32_t xsize, uint32_t y
   p->qco = 0;
   p->qco_interval_mul = 0.5f;
   p->ac_prediction = 0;
+  p->noise = 0;  // the LUT stays 0: kNoise clear
   const float m[9] = {2542.56835937500000f, -2326.53173828125000f, 44.17734527587891f,
                       -698.04852294921875f, 1012.71777343750000f,  -76.22974395751953f,
                       -827.36480712890625f, 709.83502197265625f,   451.38488769531250f};
@@ -2339,7 +2473,8 @@ extern "C" {
 
 size_t jxlr_workspace_bytes(const jxlr_frame_params* p) {
   if (check_params(p) != JXLR_OK) return 0;
-  return info_bytes(p) + xyb_buffers(p) * xyb_bytes(p) + pred_bytes(p);
+  return info_bytes(p) + xyb_buffers(p) * xyb_bytes(p) + pred_bytes(p) +
+         (p->noise ? xyb_bytes(p) : 0);
 }
 
 }  // extern "C"
@@ -2496,6 +2631,13 @@ jxlr_status make_finish_args(jxlr_ctx* ctx, const jxlr_frame_params* p, const jx
   a.out_stride = io->out_stride;
   a.thr = p->out_format == JXLR_OUT_U16_SRGB ? ctx->tables->srgb_thr16 : ctx->tables->srgb_thr8;
   a.start8 = ctx->tables->srgb_start8;
+  a.noise = p->noise;
+  a.noise_raw = nullptr;
+  for (int i = 0; i < 16; ++i) a.noise_lut[i] = p->noise_lut[i];
+  if (p->noise) {
+    if (!io->noise_raw) return JXLR_E_NULL;
+    a.noise_raw = io->noise_raw;
+  }
   *res = a;
   return JXLR_OK;
 }
@@ -2583,6 +2725,19 @@ jxlr_status jxlr_ac_prediction(jxlr_ctx* ctx, const jxlr_frame_params* p, const 
   return launch_status(hipGetLastError());
 }
 
+jxlr_status jxlr_noise_channels(jxlr_ctx* ctx, const jxlr_frame_params* p, float* raw,
+                                hipStream_t stream) {
+  if (!ctx || !raw) return JXLR_E_NULL;
+  jxlr_status st = check_params(p);
+  if (st) return st;
+  NoiseArgs a{int(p->xsize), int(p->ysize), raw, ctx->tables};
+  const int gx = int((p->xsize + 255) / 256), gy = int((p->ysize + 255) / 256);
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return JXLR_E_HIP;
+  hipLaunchKernelGGL(noise_kernel, dim3(3 * gx * gy), dim3(kNoiseThreads), 0, stream, a, gx);
+  return launch_status(hipGetLastError());
+}
+
 jxlr_status jxlr_qco_pass(jxlr_ctx* ctx, const jxlr_frame_params* p, const jxlr_frame_io* io,
                           const uint8_t* info, const float* orig, float* xyb_io, size_t stride,
                           hipStream_t stream) {
@@ -2630,9 +2785,12 @@ jxlr_status jxlr_finish(jxlr_ctx* ctx, const jxlr_frame_params* p, const jxlr_fr
   if (st) return st;
   DeviceGuard g(ctx->device);
   if (!g.ok) return JXLR_E_HIP;
-  hipLaunchKernelGGL(finish_kernel, dim3(tiles_x(p) * tiles_y(p)),
-                     dim3(fin_threads<kFinRowsFrame>()), 0, stream, a,
-                     tiles_x(p));
+  if (p->noise)
+    hipLaunchKernelGGL(finish_kernel<true>, dim3(tiles_x(p) * tiles_y(p)),
+                       dim3(fin_threads<kFinRowsFrame>()), 0, stream, a, tiles_x(p));
+  else
+    hipLaunchKernelGGL(finish_kernel<false>, dim3(tiles_x(p) * tiles_y(p)),
+                       dim3(fin_threads<kFinRowsFrame>()), 0, stream, a, tiles_x(p));
   return launch_status(hipGetLastError());
 }
 
@@ -2668,7 +2826,13 @@ jxlr_status jxlr_decode(jxlr_ctx* ctx, const jxlr_frame_params* p, const jxlr_fr
     cur = dst;
   }
   if (qco && (st = jxlr_qco_pass(ctx, p, io, info, buf[0], cur, stride, stream))) return st;
-  return jxlr_finish(ctx, p, io, cur, stride, stream);
+  if (p->noise) {
+    float* raw = reinterpret_cast<float*>(base + info_bytes(p) + xyb_buffers(p) * xyb_bytes(p) +
+                                          pred_bytes(p));
+    if ((st = jxlr_noise_channels(ctx, p, raw, stream))) return st;
+    iop.noise_raw = raw;
+  }
+  return jxlr_finish(ctx, p, &iop, cur, stride, stream);
 }
 
 }  // extern "C"
@@ -2762,7 +2926,7 @@ extern "C" {
 size_t jxlr_batch_workspace_bytes(int n, const jxlr_frame_params* p) {
   if (n <= 0 || !p) return 0;
   for (int i = 0; i < n; ++i)
-    if (check_params(&p[i]) != JXLR_OK || p[i].qco || p[i].ac_prediction) return 0;
+    if (check_params(&p[i]) != JXLR_OK || p[i].qco || p[i].ac_prediction || p[i].noise) return 0;
   return batch_layout(n, p).total;
 }
 
@@ -2774,8 +2938,8 @@ jxlr_status jxlr_batch_prepare(jxlr_ctx* ctx, int n, const jxlr_frame_params* p,
   for (int i = 0; i < n; ++i) {
     jxlr_status st = check_params(&p[i]);
     if (st) return st;
-    // the batch stages have no constraint pass and no prediction stage
-    if (p[i].qco || p[i].ac_prediction) return JXLR_E_PARAM;
+    // the batch stages have no constraint pass, prediction or noise stage
+    if (p[i].qco || p[i].ac_prediction || p[i].noise) return JXLR_E_PARAM;
   }
   const BatchLayout L = batch_layout(n, p);
   if (ws_bytes < L.total) return JXLR_E_WORKSPACE;

@@ -539,6 +539,43 @@ bool build_tables(DeviceTables* t) {
     for (int k = 0; k < c2; ++k)
       for (int j = 0; j < c2; ++j) t->pred_v[m][k][j] = float(W[k][c2 + j] * transform_scale(N, k));
   }
+  // The generator step on the state (a, b) (first, second word):
+  // a' = b, b' = u ^ b ^ (u >> 18) ^ (b >> 5) with u = a ^ (a << 23).  Its
+  // matrix by columns (images of the unit states), then squared 13 times.
+  {
+    auto step = [](uint64_t a, uint64_t b, uint64_t& na, uint64_t& nb) {
+      const uint64_t u = a ^ (a << 23);
+      na = b;
+      nb = u ^ b ^ (u >> 18) ^ (b >> 5);
+    };
+    // m[r][w]: row r, 128 bits in two words
+    uint64_t m[128][2] = {};
+    for (int j = 0; j < 128; ++j) {
+      const uint64_t a = j < 64 ? uint64_t(1) << j : 0, b = j < 64 ? 0 : uint64_t(1) << (j - 64);
+      uint64_t na, nb;
+      step(a, b, na, nb);
+      for (int r = 0; r < 128; ++r) {
+        const uint64_t bit = r < 64 ? (na >> r) & 1u : (nb >> (r - 64)) & 1u;
+        if (bit) m[r][j >> 6] |= uint64_t(1) << (j & 63);
+      }
+    }
+    for (int k = 0; k < 14; ++k) {
+      for (int r = 0; r < 128; ++r) {
+        t->noise_jump[k][r][0] = m[r][0];
+        t->noise_jump[k][r][1] = m[r][1];
+      }
+      // m = m * m over GF(2): row r of the product is the XOR of the rows j
+      // of m selected by the bits of row r
+      uint64_t sq[128][2] = {};
+      for (int r = 0; r < 128; ++r)
+        for (int j = 0; j < 128; ++j)
+          if ((m[r][j >> 6] >> (j & 63)) & 1u) {
+            sq[r][0] ^= m[j][0];
+            sq[r][1] ^= m[j][1];
+          }
+      std::memcpy(m, sq, sizeof(m));
+    }
+  }
   t->pred_sf = float(scale_f(2, 8, 1));
   t->pred_s8_1 = float(transform_scale(8, 1));
   build_mfma_operands(t);

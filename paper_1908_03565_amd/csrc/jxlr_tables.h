@@ -98,6 +98,12 @@ struct DeviceTables {
   // scale s_8(1) of their 8-point axis.
   float pred_sf;
   float pred_s8_1;
+  // Noise (K.5.2): jump-ahead of one XorShift128+ generator, whose 128-bit
+  // state (bits 0-63 the first word, 64-127 the second) advances by a map
+  // linear over GF(2); noise_jump[k][r] holds row r of that map's 2^k-th
+  // power (bit r of the advanced state is the parity of the row ANDed with
+  // the state), as two words.
+  uint64_t noise_jump[14][128][2];
 };
 
 // Fills t on the host.  Returns false if a dequantization matrix entry is not

@@ -44,6 +44,8 @@ class FrameParams(C.Structure):
         ("qco", C.c_int32),
         ("qco_interval_mul", C.c_float),
         ("ac_prediction", C.c_int32),
+        ("noise", C.c_int32),
+        ("noise_lut", C.c_float * 16),
     ]
 
 
@@ -56,6 +58,7 @@ class FrameIO(C.Structure):
         ("cfl_kx", C.c_void_p), ("cfl_kb", C.c_void_p), ("cfl_stride", C.c_size_t),
         ("out", C.c_void_p * 3), ("out_stride", C.c_size_t),
         ("ac_pred", C.c_void_p),
+        ("noise_raw", C.c_void_p),
     ]
 
 
@@ -111,6 +114,7 @@ _SIGS = {
                       C.c_int),
     "jxlr_ac_prediction": ([C.c_void_p, C.POINTER(FrameParams), C.POINTER(FrameIO), C.c_void_p,
                             C.c_void_p, C.c_void_p], C.c_int),
+    "jxlr_noise_channels": ([C.c_void_p, C.POINTER(FrameParams), C.c_void_p, C.c_void_p], C.c_int),
     "jxlr_qco_pass": ([C.c_void_p, C.POINTER(FrameParams), C.POINTER(FrameIO), C.c_void_p,
                        C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p], C.c_int),
     "jxlr_finish": ([C.c_void_p, C.POINTER(FrameParams), C.POINTER(FrameIO), C.c_void_p,
@@ -235,9 +239,10 @@ class DeviceFrame:
             setattr(c, k, getattr(self, k).clone())
         return c
 
-    def io(self, out=None, ac_pred=None):
+    def io(self, out=None, ac_pred=None, noise_raw=None):
         io = FrameIO()
         io.ac_pred = ac_pred.data_ptr() if ac_pred is not None else None
+        io.noise_raw = noise_raw.data_ptr() if noise_raw is not None else None
         for c in range(3):
             io.ac[c] = self.ac[c].data_ptr()
             io.dc[c] = self.dc[c].data_ptr()
@@ -326,9 +331,13 @@ class Context:
                                    sigma.data_ptr() if sigma is not None else None,
                                    _stream_handle(stream)), "epf_pass")
 
-    def finish(self, p, df, xyb, out, stream=None):
-        _check(lib().jxlr_finish(self.handle, C.byref(p), C.byref(df.io(out)), xyb.data_ptr(),
-                                 xyb.shape[2], _stream_handle(stream)), "finish")
+    def noise_channels(self, p, raw, stream=None):
+        _check(lib().jxlr_noise_channels(self.handle, C.byref(p), raw.data_ptr(),
+                                         _stream_handle(stream)), "noise_channels")
+
+    def finish(self, p, df, xyb, out, stream=None, noise_raw=None):
+        _check(lib().jxlr_finish(self.handle, C.byref(p), C.byref(df.io(out, noise_raw=noise_raw)),
+                                 xyb.data_ptr(), xyb.shape[2], _stream_handle(stream)), "finish")
 
     def qco_pass(self, p, df, info, xyb_orig, xyb_io, stream=None):
         _check(lib().jxlr_qco_pass(self.handle, C.byref(p), C.byref(df.io()), info.data_ptr(),

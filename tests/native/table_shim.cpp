@@ -36,4 +36,5 @@ const float* shim_pred_u() { return &g_tables.pred_u[0][0][0]; }
 const float* shim_pred_v() { return &g_tables.pred_v[0][0][0]; }
 float shim_pred_sf() { return g_tables.pred_sf; }
 float shim_pred_s8_1() { return g_tables.pred_s8_1; }
+const uint64_t* shim_noise_jump() { return &g_tables.noise_jump[0][0][0]; }
 }

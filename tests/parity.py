@@ -86,7 +86,12 @@ def gpu_stages(ctx, p, df):
         ctx.qco_pass(p, df, info, xyb, cur)
         res["qco"] = cur.cpu().numpy()
     out = ctx.empty_out(p)
-    ctx.finish(p, df, cur, out)
+    raw = None
+    if p.noise:
+        raw = ctx.empty_xyb(p)
+        ctx.noise_channels(p, raw)
+        res["noise_raw"] = raw.cpu().numpy()
+    ctx.finish(p, df, cur, out, noise_raw=raw)
     res["out"] = out.cpu().numpy()
     torch.cuda.synchronize()
     return res

@@ -1,0 +1,72 @@
+"""GPU parity of noise (K.5): the pseudorandom channels the HIP kernel makes
+(seeding, jump-ahead and stepping of the eight generators per group) against
+the FP64 oracle's, bit for bit, over frames of several groups with ragged
+edges; then the decode with noise on against the oracle's, end to end."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1908_03565_amd import workload as wl
+from tests import parity as P
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_1908_03565_amd import jxlr as J
+    return J.Context(0)
+
+
+@pytest.mark.parametrize("W,H", [(256, 256), (600, 300), (37, 530), (1, 1)])
+def test_noise_channels_bit_exact(ctx, W, H):
+    import torch
+    from paper_1908_03565_amd import jxlr as J
+    p = J.params(W, H, noise=1)
+    raw = ctx.empty_xyb(p)
+    ctx.noise_channels(p, raw)
+    torch.cuda.synchronize()
+    got = raw.cpu().numpy()
+    for y0 in range(0, H, 256):
+        for x0 in range(0, W, 256):
+            gw, gh = min(256, W - x0), min(256, H - y0)
+            want = O.noise_channels(gw, gh, x0, y0)
+            np.testing.assert_array_equal(got[:, y0:y0 + gh, x0:x0 + gw], want,
+                                          err_msg=f"group ({x0}, {y0})")
+
+
+@pytest.mark.parametrize("W,H,seed,fmt", [(300, 264, 91, 0), (131, 77, 92, 0), (300, 264, 93, 1)])
+def test_noise_end_to_end(ctx, W, H, seed, fmt):
+    from paper_1908_03565_amd import jxlr as J
+    f = wl.small(W, H, seed=seed, epf_iters=1)
+    # strengths up to 1/4 (an encoder's LUT stays small; LUT values near 1
+    # add noise of about 0.5 to XYB and drive linear RGB to 40)
+    lut = np.random.default_rng(seed).integers(0, 256, size=16) / 1024.0
+    kw = dict(f["params"], noise=1, noise_lut=lut)
+    p = J.params(W, H, out_format=fmt, **kw)
+    df = J.DeviceFrame(f)
+    gpu = P.gpu_stages(ctx, p, df)
+    q = O.params(W, H, **kw)
+    orc = O.decode_stages(q, f)
+    if fmt == 0:
+        cmp = P.compare_rgb(p, gpu, orc)
+        print({k: v for k, v in cmp.items() if k != "mask"})
+        assert cmp["max_err"] <= P.RGB_TOL
+    else:
+        # 8-bit codes: the oracle's rounding of the same linear values, up to
+        # one code where the binary32 and binary64 values straddle a boundary
+        codes = O.quantize_srgb(8, orc["rgb"]).astype(np.int64)
+        mask, _ = P.affected_mask(p, [(g, s) for _, g, s in gpu["epf"]],
+                                  [(g, s) for _, g, s in orc["epf"]])
+        mask = P.dilate(mask, range(-1, 2), range(-1, 2))
+        d = np.abs(gpu["out"].astype(np.int64) - codes)[:, ~mask]
+        print("max code diff", d.max(), "share off by one", (d > 0).mean())
+        assert d.max() <= 1 and (d > 0).mean() < 1e-3
+    # the noise moved the output, and jxlr_decode runs the same stages
+    p0 = J.params(W, H, out_format=fmt, **f["params"])
+    out0 = ctx.empty_out(p0)
+    ctx.decode(p0, df, out0, ctx.workspace(p0))
+    assert np.abs(out0.cpu().numpy().astype(np.float64) - gpu["out"]).max() > 0
+    out = ctx.empty_out(p)
+    ctx.decode(p, df, out, ctx.workspace(p))
+    np.testing.assert_array_equal(out.cpu().numpy(), gpu["out"])

@@ -105,6 +105,14 @@ def test_parameter_ranges():
         assert J.validate_maps_host(p, f) == 7, kw
         assert J.workspace_bytes(p) == 0, kw
     assert J.params(64, 64).ac_prediction == 0
+    # noise: a flag and a finite LUT
+    lut = np.zeros(16)
+    lut[3] = float("nan")
+    for kw in (dict(noise=2), dict(noise=1, noise_lut=lut)):
+        p = J.params(64, 64, **kw)
+        assert J.validate_maps_host(p, f) == 7
+        assert J.workspace_bytes(p) == 0
+    assert J.params(64, 64).noise == 0
     d = J.params(64, 64)
     assert d.qco == 0 and d.qco_interval_mul == 0.5  # C.10 defaults
 
@@ -123,6 +131,8 @@ def test_workspace_bytes():
     assert J.workspace_bytes(J.params(100, 50, epf_iters=2, qco=1)) == J.workspace_bytes(p2) + xyb
     assert J.workspace_bytes(J.params(100, 50, epf_iters=1, qco=1)) == J.workspace_bytes(p2)
     assert J.workspace_bytes(J.params(100, 50, epf_iters=0, qco=1)) == one
+    # noise adds the pseudorandom channels, one plane set
+    assert J.workspace_bytes(J.params(100, 50, epf_iters=2, noise=1)) - J.workspace_bytes(p2) == xyb
     # AC prediction adds its sums, 3 x 4 floats per block (13 x 7 blocks)
     extra = J.workspace_bytes(J.params(100, 50, epf_iters=0, ac_prediction=1)) - one
     assert 12 * 4 * 13 * 7 <= extra < 12 * 4 * 13 * 7 + 256
@@ -141,6 +151,7 @@ def test_batch_workspace_bytes():
     # the batch stages have no constraint pass
     assert J.batch_workspace_bytes(ps + [J.params(64, 64, qco=1)]) == 0
     assert J.batch_workspace_bytes(ps + [J.params(64, 64, ac_prediction=1)]) == 0
+    assert J.batch_workspace_bytes(ps + [J.params(64, 64, noise=1)]) == 0
 
 
 # --- the library's constant tables versus the oracle's --------------------
@@ -157,6 +168,7 @@ def shim(tmp_path_factory):
               "shim_dqs", "shim_a16s", "shim_a32s", "shim_b16s", "shim_b32s", "shim_pred_u",
               "shim_pred_v"):
         getattr(L, f).restype = C.POINTER(C.c_float)
+    L.shim_noise_jump.restype = C.POINTER(C.c_uint64)
     L.shim_pred_sf.restype = C.c_float
     L.shim_pred_s8_1.restype = C.c_float
     L.shim_mul.restype = C.POINTER(C.c_int32)
@@ -294,6 +306,32 @@ def test_ac_prediction_tables_match_oracle(shim):
         np.testing.assert_allclose((Vy @ S @ Vx.T) / sc, O.llf2x2_from_dc2x2(s, S), atol=1e-5)
     assert shim.shim_pred_sf() == pytest.approx(O.scalef(2, 8, 1), rel=1e-7)
     assert shim.shim_pred_s8_1() == pytest.approx(_col_scale(8)[1], rel=1e-7)
+
+
+def _gf2_apply(rows, a, b):
+    # rows: (128, 2) uint64; state (a, b) -> (a', b')
+    out = [0, 0]
+    for r in range(128):
+        par = (bin(int(rows[r, 0]) & a).count("1") + bin(int(rows[r, 1]) & b).count("1")) & 1
+        out[r >> 6] |= par << (r & 63)
+    return out[0], out[1]
+
+
+def test_noise_jump_tables(shim):
+    # power 0 is one generator step (first word a, second b: a' = b,
+    # b' = u ^ b ^ (u >> 18) ^ (b >> 5), u = a ^ (a << 23)); each power is the
+    # square of the one before
+    M = 2 ** 64 - 1
+    J = np.ctypeslib.as_array(shim.shim_noise_jump(), shape=(14 * 128 * 2,)).reshape(14, 128, 2)
+    rng = np.random.default_rng(9)
+    for _ in range(4):
+        a, b = (int(v) for v in rng.integers(0, 2 ** 63, size=2, dtype=np.int64))
+        a |= 1 << 63
+        u = (a ^ (a << 23)) & M
+        assert _gf2_apply(J[0], a, b) == (b, (u ^ b ^ (u >> 18) ^ (b >> 5)) & M)
+        for k in (0, 5, 12):
+            twice = _gf2_apply(J[k], *_gf2_apply(J[k], a, b))
+            assert twice == _gf2_apply(J[k + 1], a, b), k
 
 
 def test_schedule_cache_roundtrip(tmp_path):
