@@ -1507,6 +1507,39 @@ int orc_qco(const orc_params* p, const uint8_t* strategy, const uint8_t* qf_minu
 }
 
 /* ======================================================================= */
+/* Patches (K.3)                                                           */
+/* ======================================================================= */
+
+/* K.3: every placement adds kChannelDequant[c] times its patch's samples at
+ * its position.  place: n placements of 5 integers (x, y, xsize, ysize,
+ * offset of the patch's samples in `samples`, which hold [3][ysize][xsize]
+ * integers per patch); xsize, ysize at most 16 and the region inside the
+ * frame (C.4.6), else ORC_E_PARAM. */
+int orc_patches(const orc_params* p, const int32_t* place, int32_t n, const int32_t* samples,
+                double* xyb) {
+  static const double kChannelDequant[3] = {0.01615, 0.08875, 0.1922};
+  const int32_t W = p->xsize, H = p->ysize;
+  for (int32_t k = 0; k < n; ++k) {
+    const int32_t* q = place + 5 * k;
+    const int32_t x0 = q[0], y0 = q[1], xs = q[2], ys = q[3];
+    if (xs < 1 || ys < 1 || xs > 16 || ys > 16 || x0 < 0 || y0 < 0 || x0 + xs > W || y0 + ys > H ||
+        q[4] < 0)
+      return ORC_E_PARAM;
+  }
+  for (int32_t k = 0; k < n; ++k) {
+    const int32_t* q = place + 5 * k;
+    const int32_t x0 = q[0], y0 = q[1], xs = q[2], ys = q[3];
+    const int32_t* smp = samples + q[4];
+    for (int c = 0; c < 3; ++c)
+      for (int32_t iy = 0; iy < ys; ++iy)
+        for (int32_t ix = 0; ix < xs; ++ix)
+          xyb[(size_t)c * W * H + (size_t)(y0 + iy) * W + x0 + ix] +=
+              kChannelDequant[c] * smp[(c * ys + iy) * xs + ix];
+  }
+  return ORC_OK;
+}
+
+/* ======================================================================= */
 /* Noise (K.5)                                                             */
 /* ======================================================================= */
 
@@ -1702,6 +1735,15 @@ int orc_quantize_srgb(int32_t bits, int64_t n, const double* lin, uint16_t* out)
 int orc_decode(const orc_params* p, const int32_t* const ac[3], const int32_t* const dc[3],
                const uint8_t* strategy, const uint8_t* qf_minus_1, const uint8_t* sharpness,
                const float* cfl_kx, const float* cfl_kb, double* rgb) {
+  return orc_decode_features(p, ac, dc, strategy, qf_minus_1, sharpness, cfl_kx, cfl_kb, NULL, 0,
+                             NULL, rgb);
+}
+
+int orc_decode_features(const orc_params* p, const int32_t* const ac[3],
+                        const int32_t* const dc[3], const uint8_t* strategy,
+                        const uint8_t* qf_minus_1, const uint8_t* sharpness, const float* cfl_kx,
+                        const float* cfl_kb, const int32_t* patch_place, int32_t n_patches,
+                        const int32_t* patch_samples, double* rgb) {
   int st = check_params(p);
   if (st) return st;
   const size_t n = 3 * (size_t)p->xsize * p->ysize;
@@ -1725,6 +1767,8 @@ int orc_decode(const orc_params* p, const int32_t* const ac[3], const int32_t* c
     double* t = a; a = b; b = t;
   }
   free(r);
+  /* K.1: patches between adaptive reconstruction and Gaborish */
+  if (!st && n_patches > 0) st = orc_patches(p, patch_place, n_patches, patch_samples, a);
   if (!st && p->gab) {
     st = orc_gaborish(p, a, b);
     double* t = a; a = b; b = t;

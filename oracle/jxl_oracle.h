@@ -148,6 +148,10 @@ int orc_epf_pass(const orc_params* p, const uint8_t* strategy,
  * (all [3][ysize][xsize]; out may not alias orig). */
 int orc_qco(const orc_params* p, const uint8_t* strategy, const uint8_t* qf_minus_1,
             const double* orig, const double* filt, double* out);
+/* K.3 patches, added in place: n placements of (x, y, xsize, ysize, offset
+ * into samples), samples [3][ysize][xsize] integers per patch. */
+int orc_patches(const orc_params* p, const int32_t* place, int32_t n, const int32_t* samples,
+                double* xyb);
 /* K.5.2 SplitMix64 and the three pseudorandom channels [3][gh][gw] of the
  * group with top-left pixel (x0, y0). */
 uint64_t orc_splitmix64(uint64_t z);
@@ -175,6 +179,13 @@ int orc_decode(const orc_params* p,
                const float* cfl_kx, const float* cfl_kb,
                double* rgb);
 
+/* The same with patches (K.3) between the filters and Gaborish. */
+int orc_decode_features(const orc_params* p,
+                        const int32_t* const ac[3], const int32_t* const dc[3],
+                        const uint8_t* strategy, const uint8_t* qf_minus_1,
+                        const uint8_t* sharpness, const float* cfl_kx, const float* cfl_kb,
+                        const int32_t* patch_place, int32_t n_patches,
+                        const int32_t* patch_samples, double* rgb);
 /* Number of OpenMP threads the oracle runs with (1 when built without OpenMP). */
 int orc_num_threads(void);
 

@@ -89,6 +89,9 @@ def lib():
         L.orc_splitmix64.restype = C.c_uint64
         L.orc_noise_channels.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.c_int32, _f32p]
         L.orc_noise.argtypes = [P, _f64p, _f64p]
+        L.orc_patches.argtypes = [P, _i32p, C.c_int32, _i32p, _f64p]
+        L.orc_decode_features.argtypes = [P, ptr3, ptr3, _u8p, _u8p, _u8p, _f32p, _f32p,
+                                          C.c_void_p, C.c_int32, C.c_void_p, _f64p]
         L.orc_xyb_to_rgb.argtypes = [P, _f64p, _f64p]
         L.orc_quantize_srgb.argtypes = [C.c_int32, C.c_int64, _f64p, _u16p]
         L.orc_decode.argtypes = [P, ptr3, ptr3, _u8p, _u8p, _u8p, _f32p, _f32p, _f64p]
@@ -318,6 +321,16 @@ def qco(p, frame, orig, filt):
     return out
 
 
+def patches(p, place, samples, xyb):
+    """K.3: placements (n, 5) = (x, y, xsize, ysize, sample offset) over the
+    flat integer samples; returns the image with the patches added."""
+    out = np.array(xyb, dtype=np.float64, order="C", copy=True)
+    pl = np.ascontiguousarray(place, np.int32).reshape(-1, 5)
+    sm = np.ascontiguousarray(samples, np.int32).ravel()
+    _check(lib().orc_patches(C.byref(p), pl, len(pl), sm if sm.size else np.zeros(1, np.int32), out))
+    return out
+
+
 def splitmix64(z):
     return lib().orc_splitmix64(int(z) & (2**64 - 1))
 
@@ -359,16 +372,22 @@ def quantize_srgb(bits, lin):
 
 
 def decode(p, frame):
-    """Whole path: returns [0,1]-scaled linear RGB (3, ysize, xsize) float64."""
+    """Whole path: returns [0,1]-scaled linear RGB (3, ysize, xsize) float64.
+    Patches (K.3) come from frame["patch_place"] / frame["patch_samples"]."""
     ka, pa = _planes(frame["ac"], np.int32)
     kd, pd = _planes(frame["dc"], np.int32)
     out = np.zeros((3, p.ysize, p.xsize))
-    _check(lib().orc_decode(
+    pl = frame.get("patch_place")
+    n = 0 if pl is None else len(pl)
+    pl = np.ascontiguousarray(pl, np.int32) if n else None
+    sm = np.ascontiguousarray(frame["patch_samples"], np.int32) if n else None
+    _check(lib().orc_decode_features(
         C.byref(p), pa, pd, np.ascontiguousarray(frame["strategy"], np.uint8),
         np.ascontiguousarray(frame["qf"], np.uint8),
         np.ascontiguousarray(frame["sharpness"], np.uint8),
         np.ascontiguousarray(frame["cfl_kx"], np.float32),
-        np.ascontiguousarray(frame["cfl_kb"], np.float32), out))
+        np.ascontiguousarray(frame["cfl_kb"], np.float32),
+        pl.ctypes.data if n else None, n, sm.ctypes.data if n else None, out))
     return out
 
 
@@ -385,6 +404,9 @@ def decode_stages(p, frame):
     if p.qco and p.epf_iters > 0:
         cur = qco(p, frame, res["recon"], cur)
         res["qco"] = cur
+    if frame.get("patch_place") is not None and len(frame["patch_place"]):
+        cur = patches(p, frame["patch_place"], frame["patch_samples"], cur)
+        res["patches"] = cur
     if p.gab:
         cur = gaborish(p, cur)
     res["gab"] = cur

@@ -906,6 +906,62 @@ def test_qco_follows_the_filter_passes_in_decode():
 
 
 # --------------------------------------------------------------------------
+# Patches (K.3)
+# --------------------------------------------------------------------------
+
+K_CHANNEL_DEQUANT = (0.01615, 0.08875, 0.1922)  # printed in K.3
+
+
+def test_patch_adds_dequantized_samples():
+    W, H = 20, 12
+    p = O.params(W, H)
+    a = _rng(110).integers(-40, 41, size=(3, 2, 3))   # patch 0: 3 wide, 2 high
+    b = _rng(111).integers(-40, 41, size=(3, 16, 16))  # patch 1: the largest size
+    samples = np.concatenate([a.ravel(), b.ravel()])
+    place = np.array([[4, 5, 3, 2, 0]])
+    out = O.patches(p, place, samples, np.zeros((3, H, W)))
+    want = np.zeros((3, H, W))
+    for c in range(3):
+        want[c, 5:7, 4:7] = K_CHANNEL_DEQUANT[c] * a[c]
+    np.testing.assert_allclose(out, want, atol=1e-15)
+    # the same patch at two overlapping places and the 16x16 one: sums
+    # (a 16 x 12 patch: the frame has 12 rows)
+    place = np.array([[4, 5, 3, 2, 0], [5, 6, 3, 2, 0], [4, 0, 16, 12, 18]])
+    b12 = b[:, :12, :]
+    samples = np.concatenate([a.ravel(), b12.ravel()])
+    base = _rng(112).standard_normal((3, H, W))
+    out = O.patches(p, place, samples, base)
+    want = base.copy()
+    for c in range(3):
+        want[c, 5:7, 4:7] += K_CHANNEL_DEQUANT[c] * a[c]
+        want[c, 6:8, 5:8] += K_CHANNEL_DEQUANT[c] * a[c]
+        want[c, 0:12, 4:20] += K_CHANNEL_DEQUANT[c] * b12[c]
+    np.testing.assert_allclose(out, want, atol=1e-13)
+
+
+@pytest.mark.parametrize("bad", [[18, 0, 3, 2, 0], [0, 11, 3, 2, 0], [-1, 0, 3, 2, 0],
+                                 [0, 0, 17, 1, 0], [0, 0, 0, 2, 0]])
+def test_patch_outside_frame_is_ill_formed(bad):
+    with pytest.raises(O.OracleError):
+        O.patches(O.params(20, 12), np.array([bad]), np.zeros(3 * 17 * 2, np.int32),
+                  np.zeros((3, 12, 20)))
+
+
+def test_patches_precede_gaborish_in_decode():
+    W, H = 40, 24
+    f = _frame_of(0, W, H, _rng(113).integers(-200, 200, size=(3, 3, 5)),
+                  ac=_rng(114).integers(-4, 5, size=(3, 24, 40)).astype(np.int32))
+    f["patch_place"] = np.array([[3, 4, 5, 6, 0], [30, 10, 5, 6, 0]])
+    f["patch_samples"] = _rng(115).integers(-20, 21, size=3 * 6 * 5)
+    p = O.params(W, H, dc_mul=(0.004, 0.004, 0.004), epf_iters=1)
+    st = O.decode_stages(p, f)
+    np.testing.assert_array_equal(st["patches"], O.patches(p, f["patch_place"], f["patch_samples"],
+                                                           st["epf"][-1][0]))
+    np.testing.assert_array_equal(st["gab"], O.gaborish(p, st["patches"]))
+    np.testing.assert_allclose(O.decode(p, f), st["rgb"], atol=1e-12)
+
+
+# --------------------------------------------------------------------------
 # Noise (K.5)
 # --------------------------------------------------------------------------
 
