@@ -21,7 +21,8 @@
  * reported synchronously, before anything is enqueued.  A DctSelect map that
  * is ill-formed (C.5.4) is detected on the device: the affected 32 x 32 regions
  * are written as zero and a sticky flag is set that jxlr_get_device_status
- * reports; jxlr_validate_maps_host checks the same rules on the host first.
+ * reports (an ill-formed patch placement, K.3, sets it as well);
+ * jxlr_validate_maps_host checks the map rules on the host first.
  * On any error no output content is guaranteed.
  *
  * Threading: a context may be used from several host threads and streams at
@@ -137,6 +138,10 @@ typedef struct {
    * The batch functions reject it (JXLR_E_PARAM). */
   int32_t  noise;
   float    noise_lut[16];     /* C.4.8: u(10) / 1024 each; finite */
+  /* Patches of K.3: the number of placements in io->patch_place (0: none),
+   * added between the EPF passes (and the quantization constraint) and
+   * Gaborish.  The batch functions reject them (JXLR_E_PARAM). */
+  int32_t  num_patches;
 } jxlr_frame_params;
 
 /* Input and output planes of one frame.  With Wb = ceil(xsize/8),
@@ -179,6 +184,15 @@ typedef struct {
    * written by jxlr_noise_channels and read by jxlr_finish when p->noise;
    * may be NULL otherwise. */
   const float* noise_raw;
+  /* K.3 patches (C.4.6, already decoded): p->num_patches placements of five
+   * int32 (x, y, xsize, ysize, offset into patch_samples), each patch's
+   * samples int32 [3][ysize][xsize] at its offset; patch_samples_count
+   * elements in all.  A placement not inside the frame, larger than 16 or
+   * beyond the samples is ill-formed: skipped, with the sticky device flag
+   * set (bit 1). */
+  const int32_t* patch_place;
+  const int32_t* patch_samples;
+  size_t patch_samples_count;
 } jxlr_frame_io;
 
 typedef struct jxlr_ctx jxlr_ctx;
@@ -264,6 +278,11 @@ jxlr_status jxlr_epf_pass(jxlr_ctx* ctx, const jxlr_frame_params* p, const jxlr_
 jxlr_status jxlr_qco_pass(jxlr_ctx* ctx, const jxlr_frame_params* p, const jxlr_frame_io* io,
                           const uint8_t* info, const float* xyb_orig, float* xyb_io,
                           size_t xyb_stride, hipStream_t stream);
+
+/* K.3: adds the patches of io to the XYB planes in place (float atomics, so
+ * overlapping placements may sum in any order). */
+jxlr_status jxlr_patches(jxlr_ctx* ctx, const jxlr_frame_params* p, const jxlr_frame_io* io,
+                         float* xyb, size_t xyb_stride, hipStream_t stream);
 
 /* K.5.2: the three pseudorandom channels of every 256x256 group of the frame
  * (frame-sized planes, float [3][ysize][xsize], row stride xsize, device

@@ -2019,6 +2019,43 @@ __device__ __attribute__((always_inline)) inline void finish_tile(const FinishAr
 }
 
 // ---------------------------------------------------------------------------
+// Patches (K.3).  One workgroup per placement, one thread per patch sample
+// (at most 16x16); each adds its three dequantized samples to the XYB frame
+// with atomic adds (placements may overlap).  A placement outside the frame,
+// of a size above 16 or with samples beyond the array is skipped and sets
+// the sticky device flag.
+
+struct PatchArgs {
+  int W, H;
+  float* xyb;
+  size_t stride;
+  const int32_t* place;    // 5 per placement: x, y, xsize, ysize, sample offset
+  const int32_t* samples;  // [3][ysize][xsize] per patch
+  size_t samples_count;
+  int* status;
+};
+
+__global__ __launch_bounds__(256) void patches_kernel(PatchArgs a) {
+  const int32_t* q = a.place + 5 * size_t(blockIdx.x);
+  const int x0 = q[0], y0 = q[1], xs = q[2], ys = q[3], off = q[4];
+  const bool ok = xs >= 1 && ys >= 1 && xs <= 16 && ys <= 16 && x0 >= 0 && y0 >= 0 &&
+                  x0 <= a.W - xs && y0 <= a.H - ys && off >= 0 &&
+                  size_t(off) + size_t(3 * xs * ys) <= a.samples_count;
+  if (!ok) {
+    if (threadIdx.x == 0) atomicOr(a.status, 2);
+    return;
+  }
+  const int ix = threadIdx.x & 15, iy = threadIdx.x >> 4;
+  if (ix >= xs || iy >= ys) return;
+  const float kDequant[3] = {0.01615f, 0.08875f, 0.1922f};
+  const size_t plane = size_t(a.H) * a.stride;
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+    atomicAdd(a.xyb + c * plane + size_t(y0 + iy) * a.stride + x0 + ix,
+              kDequant[c] * float(a.samples[off + (c * ys + iy) * xs + ix]));
+}
+
+// ---------------------------------------------------------------------------
 // Noise channels (K.5.2).  One workgroup per 256x256 group and channel; each
 // thread runs one of the eight generators over 16 rows: it seeds the
 // generator (SplitMix64 chain), jumps it ahead to its first step with the
@@ -2303,6 +2340,7 @@ jxlr_status check_params(const jxlr_frame_params* p) {
   if (p->ac_prediction < 0 || p->ac_prediction > 1 || (p->ac_prediction && !el0))
     return JXLR_E_PARAM;
   if (p->noise < 0 || p->noise > 1) return JXLR_E_PARAM;
+  if (p->num_patches < 0) return JXLR_E_PARAM;
   for (int i = 0; i < 16; ++i)
     if (!std::isfinite(p->noise_lut[i])) return JXLR_E_PARAM;
   if (p->qco && (!el0 || !(p->qco_interval_mul >= 0.0f) || !std::isfinite(p->qco_interval_mul)))
@@ -2725,6 +2763,22 @@ jxlr_status jxlr_ac_prediction(jxlr_ctx* ctx, const jxlr_frame_params* p, const 
   return launch_status(hipGetLastError());
 }
 
+jxlr_status jxlr_patches(jxlr_ctx* ctx, const jxlr_frame_params* p, const jxlr_frame_io* io,
+                         float* xyb, size_t stride, hipStream_t stream) {
+  if (!ctx || !io || !xyb) return JXLR_E_NULL;
+  jxlr_status st = check_params(p);
+  if (st) return st;
+  if (stride < p->xsize) return JXLR_E_SIZE;
+  if (p->num_patches == 0) return JXLR_OK;
+  if (!io->patch_place || !io->patch_samples) return JXLR_E_NULL;
+  PatchArgs a{int(p->xsize), int(p->ysize), xyb, stride, io->patch_place, io->patch_samples,
+              io->patch_samples_count, ctx->status};
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return JXLR_E_HIP;
+  hipLaunchKernelGGL(patches_kernel, dim3(p->num_patches), dim3(256), 0, stream, a);
+  return launch_status(hipGetLastError());
+}
+
 jxlr_status jxlr_noise_channels(jxlr_ctx* ctx, const jxlr_frame_params* p, float* raw,
                                 hipStream_t stream) {
   if (!ctx || !raw) return JXLR_E_NULL;
@@ -2826,6 +2880,7 @@ jxlr_status jxlr_decode(jxlr_ctx* ctx, const jxlr_frame_params* p, const jxlr_fr
     cur = dst;
   }
   if (qco && (st = jxlr_qco_pass(ctx, p, io, info, buf[0], cur, stride, stream))) return st;
+  if (p->num_patches > 0 && (st = jxlr_patches(ctx, p, io, cur, stride, stream))) return st;
   if (p->noise) {
     float* raw = reinterpret_cast<float*>(base + info_bytes(p) + xyb_buffers(p) * xyb_bytes(p) +
                                           pred_bytes(p));
@@ -2926,7 +2981,9 @@ extern "C" {
 size_t jxlr_batch_workspace_bytes(int n, const jxlr_frame_params* p) {
   if (n <= 0 || !p) return 0;
   for (int i = 0; i < n; ++i)
-    if (check_params(&p[i]) != JXLR_OK || p[i].qco || p[i].ac_prediction || p[i].noise) return 0;
+    if (check_params(&p[i]) != JXLR_OK || p[i].qco || p[i].ac_prediction || p[i].noise ||
+        p[i].num_patches)
+      return 0;
   return batch_layout(n, p).total;
 }
 
@@ -2938,8 +2995,8 @@ jxlr_status jxlr_batch_prepare(jxlr_ctx* ctx, int n, const jxlr_frame_params* p,
   for (int i = 0; i < n; ++i) {
     jxlr_status st = check_params(&p[i]);
     if (st) return st;
-    // the batch stages have no constraint pass, prediction or noise stage
-    if (p[i].qco || p[i].ac_prediction || p[i].noise) return JXLR_E_PARAM;
+    // the batch stages have no constraint pass, prediction, patch or noise stage
+    if (p[i].qco || p[i].ac_prediction || p[i].noise || p[i].num_patches) return JXLR_E_PARAM;
   }
   const BatchLayout L = batch_layout(n, p);
   if (ws_bytes < L.total) return JXLR_E_WORKSPACE;

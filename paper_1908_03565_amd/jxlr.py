@@ -46,6 +46,7 @@ class FrameParams(C.Structure):
         ("ac_prediction", C.c_int32),
         ("noise", C.c_int32),
         ("noise_lut", C.c_float * 16),
+        ("num_patches", C.c_int32),
     ]
 
 
@@ -59,6 +60,8 @@ class FrameIO(C.Structure):
         ("out", C.c_void_p * 3), ("out_stride", C.c_size_t),
         ("ac_pred", C.c_void_p),
         ("noise_raw", C.c_void_p),
+        ("patch_place", C.c_void_p), ("patch_samples", C.c_void_p),
+        ("patch_samples_count", C.c_size_t),
     ]
 
 
@@ -114,6 +117,8 @@ _SIGS = {
                       C.c_int),
     "jxlr_ac_prediction": ([C.c_void_p, C.POINTER(FrameParams), C.POINTER(FrameIO), C.c_void_p,
                             C.c_void_p, C.c_void_p], C.c_int),
+    "jxlr_patches": ([C.c_void_p, C.POINTER(FrameParams), C.POINTER(FrameIO), C.c_void_p,
+                      C.c_size_t, C.c_void_p], C.c_int),
     "jxlr_noise_channels": ([C.c_void_p, C.POINTER(FrameParams), C.c_void_p, C.c_void_p], C.c_int),
     "jxlr_qco_pass": ([C.c_void_p, C.POINTER(FrameParams), C.POINTER(FrameIO), C.c_void_p,
                        C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p], C.c_int),
@@ -230,6 +235,11 @@ class DeviceFrame:
         self.sharpness = t(frame["sharpness"], np.uint8)
         self.cfl_kx = t(frame["cfl_kx"], np.float32)
         self.cfl_kb = t(frame["cfl_kb"], np.float32)
+        # K.3 patches, if the frame has any
+        pl = frame.get("patch_place")
+        self.patch_place = t(pl, np.int32) if pl is not None and len(pl) else None
+        self.patch_samples = (t(frame["patch_samples"], np.int32)
+                              if self.patch_place is not None else None)
 
     def clone(self):
         """A copy in distinct device memory."""
@@ -237,12 +247,18 @@ class DeviceFrame:
         c.xsize, c.ysize = self.xsize, self.ysize
         for k in ("ac", "dc", "strategy", "qf", "sharpness", "cfl_kx", "cfl_kb"):
             setattr(c, k, getattr(self, k).clone())
+        c.patch_place = None if self.patch_place is None else self.patch_place.clone()
+        c.patch_samples = None if self.patch_samples is None else self.patch_samples.clone()
         return c
 
     def io(self, out=None, ac_pred=None, noise_raw=None):
         io = FrameIO()
         io.ac_pred = ac_pred.data_ptr() if ac_pred is not None else None
         io.noise_raw = noise_raw.data_ptr() if noise_raw is not None else None
+        if getattr(self, "patch_place", None) is not None:
+            io.patch_place = self.patch_place.data_ptr()
+            io.patch_samples = self.patch_samples.data_ptr()
+            io.patch_samples_count = self.patch_samples.numel()
         for c in range(3):
             io.ac[c] = self.ac[c].data_ptr()
             io.dc[c] = self.dc[c].data_ptr()
@@ -330,6 +346,10 @@ class Context:
                                    guide.data_ptr() if guide is not None else None,
                                    sigma.data_ptr() if sigma is not None else None,
                                    _stream_handle(stream)), "epf_pass")
+
+    def patches(self, p, df, xyb, stream=None):
+        _check(lib().jxlr_patches(self.handle, C.byref(p), C.byref(df.io()), xyb.data_ptr(),
+                                  xyb.shape[2], _stream_handle(stream)), "patches")
 
     def noise_channels(self, p, raw, stream=None):
         _check(lib().jxlr_noise_channels(self.handle, C.byref(p), raw.data_ptr(),

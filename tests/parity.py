@@ -85,6 +85,11 @@ def gpu_stages(ctx, p, df):
     if p.qco and p.epf_iters > 0:
         ctx.qco_pass(p, df, info, xyb, cur)
         res["qco"] = cur.cpu().numpy()
+    if p.num_patches:
+        if cur is xyb:  # keep the reconstruction as it was
+            cur = xyb.clone()
+        ctx.patches(p, df, cur)
+        res["patches"] = cur.cpu().numpy()
     out = ctx.empty_out(p)
     raw = None
     if p.noise:
