@@ -1605,7 +1605,11 @@ void orc_noise_channels(int32_t gw, int32_t gh, int32_t x0, int32_t y0, float* o
  * N_G = (0.01 A_G + 0.99 A_B) S_G are added: X += N_R - N_G,
  * Y += N_R + N_G, B += 0.935669 (N_R + N_G).  Readings: the channels are
  * generated at the group's size, and the 5x5 kernel mirrors at the group's
- * edges; the fractional part is taken before the integer part is clamped. */
+ * edges; the clamp of the integer part to [0, 14] bounds the scaled input
+ * to [0, 15] before the split (the strength is the LUT interpolated on
+ * [0, 15] and held at its end values outside; taking the fraction before the
+ * clamp would make the strength jump from LUT[0] to LUT[1] where the input
+ * crosses 0). */
 int orc_noise(const orc_params* p, const double* in, double* out) {
   int st = check_params(p);
   if (st) return st;
@@ -1633,11 +1637,11 @@ int orc_noise(const orc_params* p, const double* in, double* out) {
           double S[2];
           const double inp[2] = {Y + X, Y - X};
           for (int k = 0; k < 2; ++k) {
-            const double sc = inp[k] * 14.0;
+            double sc = inp[k] * 14.0;
+            sc = sc < 0.0 ? 0.0 : sc > 15.0 ? 15.0 : sc;
             double in_int = floor(sc);
-            const double in_frac = sc - in_int;
-            if (in_int < 0.0) in_int = 0.0;
             if (in_int > 14.0) in_int = 14.0;
+            const double in_frac = sc - in_int;
             const int ii = (int)in_int;
             double v = p->noise_lut[ii] * (1.0 - in_frac) + p->noise_lut[ii + 1] * in_frac;
             S[k] = v < 0.0 ? 0.0 : v > 1.0 ? 1.0 : v;

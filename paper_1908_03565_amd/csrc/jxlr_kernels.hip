@@ -1865,10 +1865,11 @@ __device__ inline void noise_add(const FinishArgs& a, int x, int y, float (&v)[3
   float S[2];
 #pragma unroll
   for (int k = 0; k < 2; ++k) {
-    const float sc = in[k] * 14.0f;
-    const float fl = floorf(sc);
+    // the LUT interpolated on [0, 15] and held at its ends outside
+    const float sc = fminf(fmaxf(in[k] * 14.0f, 0.0f), 15.0f);
+    const float fl = fminf(floorf(sc), 14.0f);
     const float fr = sc - fl;
-    const int ii = int(fminf(fmaxf(fl, 0.0f), 14.0f));
+    const int ii = int(fl);
     S[k] = fminf(fmaxf(fmaf(lut[ii + 1], fr, lut[ii] * (1.0f - fr)), 0.0f), 1.0f);
   }
   const float nr = fmaf(0.01f * A[0], S[0], 0.99f * A[2] * S[0]);

@@ -285,6 +285,11 @@ class Context:
     """A jxlr context on one HIP device."""
 
     def __init__(self, device=0):
+        import torch
+        # torch's HIP runtime is initialised first: the buffers and streams
+        # this binding hands to the library are torch's, and a runtime that
+        # the library brought up first can leave torch without devices
+        torch.cuda.init()
         self.device = device
         h = C.c_void_p()
         _check(lib().jxlr_create(C.byref(h), int(device)), "create")

@@ -1040,10 +1040,8 @@ def test_noise_adds_lut_modulated_laplacian_of_the_channels():
     A[:, :, 256:] = _noise_A(32, H, 256, 0)
 
     def strength(v):
-        sc = 14.0 * v
-        f = sc - np.floor(sc)
-        i = np.clip(np.floor(sc), 0, 14).astype(int)
-        return np.clip(lut[i] * (1 - f) + lut[i + 1] * f, 0.0, 1.0)
+        # the LUT as a piecewise-linear function on [0, 15], held outside
+        return np.clip(np.interp(np.clip(14.0 * v, 0.0, 15.0), np.arange(16), lut), 0.0, 1.0)
 
     SR, SG = strength(xyb[1] + xyb[0]), strength(xyb[1] - xyb[0])
     NR = (0.01 * A[0] + 0.99 * A[2]) * SR
@@ -1053,6 +1051,14 @@ def test_noise_adds_lut_modulated_laplacian_of_the_channels():
     np.testing.assert_allclose(out[2] - xyb[2], 0.935669 * (NR + NG), atol=1e-12)
     inR = xyb[1] + xyb[0]
     assert np.abs(A).std() > 0.1 and (inR < 0).any() and (14 * inR >= 15).any()
+    # the strength is continuous where the input crosses 0 and 15 / 14
+    # (X = 0, so both inputs are Y; the same pixels just below and above)
+    pn = O.params(2, 1, noise=1, noise_lut=lut)
+    lo = np.zeros((3, 1, 2))
+    hi = np.zeros((3, 1, 2))
+    lo[1, 0] = [-1e-12, 15 / 14 - 1e-12]
+    hi[1, 0] = [1e-12, 15 / 14 + 1e-12]
+    np.testing.assert_allclose(O.noise(pn, lo) - lo, O.noise(pn, hi) - hi, atol=1e-9)
     # a zero LUT adds nothing
     np.testing.assert_array_equal(O.noise(O.params(W, H, noise=1), xyb), xyb)
 
