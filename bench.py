@@ -69,22 +69,22 @@ def log(msg):
 PMC_COPY_SCALE = {"FETCH_SIZE": 2.0, "WRITE_SIZE": 1.0}
 PMC_SOURCES = ("paper_1908_03565_amd/csrc/jxlr_kernels.hip", "paper_1908_03565_amd/csrc/jxlr_tables.cpp",
                "paper_1908_03565_amd/csrc/jxlr_tables.h", "paper_1908_03565_amd/csrc/gen_dct_consts.py")
-PMC_SOURCES_SHA256 = "d452e449fe0c50b7fef33da888453256334d835cbdcb31c650ce3d3ed7dc0e93"
+PMC_SOURCES_SHA256 = "98f5a478c42ce531bfd446b6d0411c159851b2e0b14b28f7ad6c891d20542631"
 # (workload name, kernel) -> (FETCH_SIZE KiB, WRITE_SIZE KiB) per dispatch
 PMC_KIB = {
-    ("c2_2048x2048_mixed_epf2", "epf_kernel"): (25440.4, 49152.0),
-    ("c2_2048x2048_mixed_epf2", "recon_kernel"): (25796.2, 49481.3),
-    ("c2_2048x2048_mixed_epf2", "finish_kernel"): (24870.3, 49152.0),
-    ("c2_2048x2048_mixed_epf2_qco", "epf_kernel"): (25440.6, 49152.0),
-    ("c2_2048x2048_mixed_epf2_qco", "qco_kernel"): (70786.2, 49152.0),
-    ("c3_4096x4096_half_dct32", "epf_kernel"): (101222.8, 196608.0),
-    ("c3_4096x4096_half_dct32", "recon_kernel"): (101298.8, 197254.4),
-    ("c3_4096x4096_half_dct32", "finish_kernel"): (98883.4, 196608.0),
-    ("c4_batch64_loguniform_256_3072_epf1_u8srgb", "epf_batch_kernel"): (528697.4, 1052228.1),
-    ("c4_batch64_loguniform_256_3072_epf1_u8srgb", "recon_batch_kernel"): (536292.0, 1061586.0),
-    ("c4_batch64_loguniform_256_3072_epf1_u8srgb", "finish_batch_kernel"): (526398.5, 263629.0),
-    ("c1x1024_256x256_dct8", "recon_batch_kernel"): (401017.0, 786436.0),
-    ("c1x1024_256x256_dct8", "finish_batch_kernel"): (845047.3, 786432.0),
+    ("c2_2048x2048_mixed_epf2", "epf_kernel"): (25442.3, 49152.0),
+    ("c2_2048x2048_mixed_epf2", "recon_kernel"): (25809.6, 49481.8),
+    ("c2_2048x2048_mixed_epf2", "finish_kernel"): (24911.6, 49152.0),
+    ("c2_2048x2048_mixed_epf2_qco", "epf_kernel"): (25442.6, 49152.0),
+    ("c2_2048x2048_mixed_epf2_qco", "qco_kernel"): (70870.1, 49152.0),
+    ("c3_4096x4096_half_dct32", "epf_kernel"): (101209.5, 196608.0),
+    ("c3_4096x4096_half_dct32", "recon_kernel"): (101298.4, 197253.3),
+    ("c3_4096x4096_half_dct32", "finish_kernel"): (98879.1, 196608.0),
+    ("c4_batch64_loguniform_256_3072_epf1_u8srgb", "epf_batch_kernel"): (528700.8, 1052239.1),
+    ("c4_batch64_loguniform_256_3072_epf1_u8srgb", "recon_batch_kernel"): (536210.5, 1058835.2),
+    ("c4_batch64_loguniform_256_3072_epf1_u8srgb", "finish_batch_kernel"): (526386.1, 263633.6),
+    ("c1x1024_256x256_dct8", "recon_batch_kernel"): (401019.3, 786434.0),
+    ("c1x1024_256x256_dct8", "finish_batch_kernel"): (845306.3, 786432.0),
 }
 
 
