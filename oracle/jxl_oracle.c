@@ -77,6 +77,7 @@ void orc_params_default(orc_params* p, int32_t xsize, int32_t ysize) {
   p->qco_interval_mul = 0.5;
   p->ac_prediction = 0;
   p->noise = 0;  /* kNoise clear; the LUT is read only when it is set (C.4.8) */
+  p->dot_colour_quant[0] = p->dot_colour_quant[1] = p->dot_colour_quant[2] = 0.0;
 }
 
 int orc_num_threads(void) {
@@ -1540,6 +1541,59 @@ int orc_patches(const orc_params* p, const int32_t* place, int32_t n, const int3
 }
 
 /* ======================================================================= */
+/* Dots (K.2)                                                              */
+/* ======================================================================= */
+
+/* K.2.1 LinDequant. */
+static double lin_dequant(double x, double lo, double hi, double levels) {
+  return (hi - lo) / levels * (x + 0.5) + lo;
+}
+
+/* K.2: n quantized dots (C.4.5), 10 integers each: x, y (times 5), sigma_x,
+ * sigma_y, angle, sign_intensity, intensity[3], is_circle; each dequantized
+ * (K.2.1) and added as a Gaussian over the 5 x 5 samples around
+ * (floor(x), floor(y)) (K.2.2), in place.  Readings: kColourQuant, which the
+ * draft never gives, is p->dot_colour_quant; a set sign bit negates its
+ * channel's intensity (the printed assignment leaves it as it is); samples
+ * of the window outside the frame are skipped. */
+int orc_dots(const orc_params* p, const int32_t* dots, int32_t n, double* xyb) {
+  const int32_t W = p->xsize, H = p->ysize;
+  const double kPi = 3.14159265358979323846;
+  for (int32_t k = 0; k < n; ++k) {
+    const int32_t* q = dots + 10 * k;
+    const double ex = q[0] / 5.0, ey = q[1] / 5.0;
+    double angle, sx, sy;
+    if (q[9]) {
+      angle = 0.0;
+      sx = sy = lin_dequant(q[2], 0.1, 3.1, 16);
+    } else {
+      angle = lin_dequant(q[4], 0.0, kPi, 8);
+      sx = lin_dequant(q[2], 0.1, 3.1, 16);
+      sy = lin_dequant(q[3], 0.1, 3.1, 16);
+    }
+    const double vx = sx * sx, vy = sy * sy;
+    double inten[3];
+    for (int c = 0; c < 3; ++c) {
+      inten[c] = p->dot_colour_quant[c] * (q[6 + c] + 0.5);
+      if (q[5] & (1 << c)) inten[c] = -inten[c];
+    }
+    inten[2] += 0.935669 * inten[1];
+    const int32_t fx = (int32_t)floor(ex), fy = (int32_t)floor(ey);
+    const double ca = cos(angle), sa = sin(angle);
+    for (int32_t iy = fy - 2; iy <= fy + 2; ++iy)
+      for (int32_t ix = fx - 2; ix <= fx + 2; ++ix) {
+        if (ix < 0 || iy < 0 || ix >= W || iy >= H) continue;
+        const double rx = ca * (ix - ex) + sa * (iy - ey);
+        const double ry = -sa * (ix - ex) + ca * (iy - ey);
+        const double md = rx * rx / vx + ry * ry / vy;
+        const double g = exp(-0.5 * md);
+        for (int c = 0; c < 3; ++c) xyb[(size_t)c * W * H + (size_t)iy * W + ix] += inten[c] * g;
+      }
+  }
+  return ORC_OK;
+}
+
+/* ======================================================================= */
 /* Noise (K.5)                                                             */
 /* ======================================================================= */
 
@@ -1740,14 +1794,15 @@ int orc_decode(const orc_params* p, const int32_t* const ac[3], const int32_t* c
                const uint8_t* strategy, const uint8_t* qf_minus_1, const uint8_t* sharpness,
                const float* cfl_kx, const float* cfl_kb, double* rgb) {
   return orc_decode_features(p, ac, dc, strategy, qf_minus_1, sharpness, cfl_kx, cfl_kb, NULL, 0,
-                             NULL, rgb);
+                             NULL, NULL, 0, rgb);
 }
 
 int orc_decode_features(const orc_params* p, const int32_t* const ac[3],
                         const int32_t* const dc[3], const uint8_t* strategy,
                         const uint8_t* qf_minus_1, const uint8_t* sharpness, const float* cfl_kx,
                         const float* cfl_kb, const int32_t* patch_place, int32_t n_patches,
-                        const int32_t* patch_samples, double* rgb) {
+                        const int32_t* patch_samples, const int32_t* dots, int32_t n_dots,
+                        double* rgb) {
   int st = check_params(p);
   if (st) return st;
   const size_t n = 3 * (size_t)p->xsize * p->ysize;
@@ -1777,7 +1832,8 @@ int orc_decode_features(const orc_params* p, const int32_t* const ac[3],
     st = orc_gaborish(p, a, b);
     double* t = a; a = b; b = t;
   }
-  /* K.1: noise after Gaborish */
+  /* K.1: dots, then noise, after Gaborish */
+  if (!st && n_dots > 0) st = orc_dots(p, dots, n_dots, a);
   if (!st && p->noise) {
     st = orc_noise(p, a, b);
     double* t = a; a = b; b = t;

@@ -77,6 +77,7 @@ typedef struct {
   int32_t ac_prediction;       /* Annex H (kSkipPredictLF clear); 0 = skipped */
   int32_t noise;               /* kNoise (K.5); 0 = skipped */
   double  noise_lut[16];       /* C.4.8 LUT, each u(10) / 1024 */
+  double  dot_colour_quant[3]; /* kColourQuant of K.2.1 (not given by the draft) */
 } orc_params;
 
 /* Fills the defaults the draft gives for every field (C.4, C.10, L.2, A.4.5). */
@@ -152,6 +153,9 @@ int orc_qco(const orc_params* p, const uint8_t* strategy, const uint8_t* qf_minu
  * into samples), samples [3][ysize][xsize] integers per patch. */
 int orc_patches(const orc_params* p, const int32_t* place, int32_t n, const int32_t* samples,
                 double* xyb);
+/* K.2 dots, added in place: n quantized dots of 10 integers (x, y, sigma_x,
+ * sigma_y, angle, sign_intensity, intensity[3], is_circle). */
+int orc_dots(const orc_params* p, const int32_t* dots, int32_t n, double* xyb);
 /* K.5.2 SplitMix64 and the three pseudorandom channels [3][gh][gw] of the
  * group with top-left pixel (x0, y0). */
 uint64_t orc_splitmix64(uint64_t z);
@@ -179,13 +183,15 @@ int orc_decode(const orc_params* p,
                const float* cfl_kx, const float* cfl_kb,
                double* rgb);
 
-/* The same with patches (K.3) between the filters and Gaborish. */
+/* The same with patches (K.3) between the filters and Gaborish, and dots
+ * (K.2) between Gaborish and the noise. */
 int orc_decode_features(const orc_params* p,
                         const int32_t* const ac[3], const int32_t* const dc[3],
                         const uint8_t* strategy, const uint8_t* qf_minus_1,
                         const uint8_t* sharpness, const float* cfl_kx, const float* cfl_kb,
                         const int32_t* patch_place, int32_t n_patches,
-                        const int32_t* patch_samples, double* rgb);
+                        const int32_t* patch_samples, const int32_t* dots, int32_t n_dots,
+                        double* rgb);
 /* Number of OpenMP threads the oracle runs with (1 when built without OpenMP). */
 int orc_num_threads(void);
 

@@ -40,6 +40,7 @@ class OrcParams(C.Structure):
         ("ac_prediction", C.c_int32),
         ("noise", C.c_int32),
         ("noise_lut", C.c_double * 16),
+        ("dot_colour_quant", C.c_double * 3),
     ]
 
 
@@ -91,7 +92,9 @@ def lib():
         L.orc_noise.argtypes = [P, _f64p, _f64p]
         L.orc_patches.argtypes = [P, _i32p, C.c_int32, _i32p, _f64p]
         L.orc_decode_features.argtypes = [P, ptr3, ptr3, _u8p, _u8p, _u8p, _f32p, _f32p,
-                                          C.c_void_p, C.c_int32, C.c_void_p, _f64p]
+                                          C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p,
+                                          C.c_int32, _f64p]
+        L.orc_dots.argtypes = [P, _i32p, C.c_int32, _f64p]
         L.orc_xyb_to_rgb.argtypes = [P, _f64p, _f64p]
         L.orc_quantize_srgb.argtypes = [C.c_int32, C.c_int64, _f64p, _u16p]
         L.orc_decode.argtypes = [P, ptr3, ptr3, _u8p, _u8p, _u8p, _f32p, _f32p, _f64p]
@@ -331,6 +334,14 @@ def patches(p, place, samples, xyb):
     return out
 
 
+def dots(p, quantized, xyb):
+    """K.2: quantized dots (n, 10) added to a copy of the image."""
+    out = np.array(xyb, dtype=np.float64, order="C", copy=True)
+    q = np.ascontiguousarray(quantized, np.int32).reshape(-1, 10)
+    _check(lib().orc_dots(C.byref(p), q if len(q) else np.zeros((1, 10), np.int32), len(q), out))
+    return out
+
+
 def splitmix64(z):
     return lib().orc_splitmix64(int(z) & (2**64 - 1))
 
@@ -381,13 +392,17 @@ def decode(p, frame):
     n = 0 if pl is None else len(pl)
     pl = np.ascontiguousarray(pl, np.int32) if n else None
     sm = np.ascontiguousarray(frame["patch_samples"], np.int32) if n else None
+    dt = frame.get("dots")
+    nd = 0 if dt is None else len(dt)
+    dt = np.ascontiguousarray(dt, np.int32) if nd else None
     _check(lib().orc_decode_features(
         C.byref(p), pa, pd, np.ascontiguousarray(frame["strategy"], np.uint8),
         np.ascontiguousarray(frame["qf"], np.uint8),
         np.ascontiguousarray(frame["sharpness"], np.uint8),
         np.ascontiguousarray(frame["cfl_kx"], np.float32),
         np.ascontiguousarray(frame["cfl_kb"], np.float32),
-        pl.ctypes.data if n else None, n, sm.ctypes.data if n else None, out))
+        pl.ctypes.data if n else None, n, sm.ctypes.data if n else None,
+        dt.ctypes.data if nd else None, nd, out))
     return out
 
 
@@ -410,6 +425,9 @@ def decode_stages(p, frame):
     if p.gab:
         cur = gaborish(p, cur)
     res["gab"] = cur
+    if frame.get("dots") is not None and len(frame["dots"]):
+        cur = dots(p, frame["dots"], cur)
+        res["dots"] = cur
     if p.noise:
         cur = noise(p, cur)
         res["noise"] = cur

@@ -962,6 +962,68 @@ def test_patches_precede_gaborish_in_decode():
 
 
 # --------------------------------------------------------------------------
+# Dots (K.2)
+# --------------------------------------------------------------------------
+
+def _dot(x5, y5, sx, sy, angle, sign, inten, circle):
+    return [x5, y5, sx, sy, angle, sign, inten[0], inten[1], inten[2], circle]
+
+
+def test_circle_dot_is_an_isotropic_gaussian():
+    # a circle at (10.4, 7.2): radius = 3 / 16 (sigma + 0.5) + 0.1; every
+    # sample of the 5x5 window around (10, 7) gets I exp(-d^2 / (2 r^2))
+    W, H = 24, 16
+    kq = (0.5, 0.25, 2.0)
+    p = O.params(W, H, dot_colour_quant=kq)
+    d = _dot(52, 36, 7, 7, 3, 0b010, (3, 5, 1), 1)
+    out = O.dots(p, [d], np.zeros((3, H, W)))
+    r = 3.0 / 16 * 7.5 + 0.1
+    inten = np.array([kq[0] * 3.5, -kq[1] * 5.5, kq[2] * 1.5])
+    inten[2] += 0.935669 * inten[1]
+    want = np.zeros((3, H, W))
+    for iy in range(5, 10):
+        for ix in range(8, 13):
+            g = np.exp(-((ix - 10.4) ** 2 + (iy - 7.2) ** 2) / (2 * r * r))
+            want[:, iy, ix] = inten * g
+    np.testing.assert_allclose(out, want, atol=1e-14)
+
+
+def test_ellipse_dot_axes_and_window():
+    # an ellipse of angle pi/16 (quantized 0): along its long axis the
+    # Gaussian falls with sx, across with sy; a dot at the corner keeps only
+    # the samples inside the frame
+    W, H = 30, 20
+    p = O.params(W, H, dot_colour_quant=(1.0, 1.0, 1.0))
+    d = _dot(75, 50, 15, 3, 0, 0, (0, 1, 0), 0)  # centre (15, 10)
+    out = O.dots(p, [d], np.zeros((3, H, W)))
+    sx, sy = 3.0 / 16 * 15.5 + 0.1, 3.0 / 16 * 3.5 + 0.1
+    th = np.pi / 8 * 0.5
+    for iy in range(8, 13):
+        for ix in range(13, 18):
+            dx, dy = ix - 15, iy - 10
+            along = np.cos(th) * dx + np.sin(th) * dy
+            across = -np.sin(th) * dx + np.cos(th) * dy
+            g = np.exp(-0.5 * (along ** 2 / sx ** 2 + across ** 2 / sy ** 2))
+            assert out[1, iy, ix] == pytest.approx(1.5 * g, rel=1e-12)
+    assert np.count_nonzero(out[1]) == 25
+    corner = O.dots(p, [_dot(0, 0, 15, 15, 0, 0, (0, 1, 0), 1)], np.zeros((3, H, W)))
+    assert np.count_nonzero(corner[1]) == 9 and corner[1, :3, :3].all()
+
+
+def test_dots_follow_gaborish_and_precede_noise():
+    W, H = 40, 24
+    f = _frame_of(0, W, H, _rng(130).integers(-200, 200, size=(3, 3, 5)),
+                  ac=_rng(131).integers(-4, 5, size=(3, 24, 40)).astype(np.int32))
+    f["dots"] = np.array([_dot(60, 40, 9, 4, 5, 1, (2, 7, 3), 0), _dot(150, 90, 12, 12, 0, 4, (1, 3, 2), 1)])
+    p = O.params(W, H, dc_mul=(0.004, 0.004, 0.004), epf_iters=1, noise=1,
+                 noise_lut=np.full(16, 0.1), dot_colour_quant=(0.01, 0.02, 0.03))
+    st = O.decode_stages(p, f)
+    np.testing.assert_array_equal(st["dots"], O.dots(p, f["dots"], st["gab"]))
+    np.testing.assert_array_equal(st["noise"], O.noise(p, st["dots"]))
+    np.testing.assert_allclose(O.decode(p, f), st["rgb"], atol=1e-12)
+
+
+# --------------------------------------------------------------------------
 # Noise (K.5)
 # --------------------------------------------------------------------------
 
