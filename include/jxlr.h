@@ -142,6 +142,13 @@ typedef struct {
    * added between the EPF passes (and the quantization constraint) and
    * Gaborish.  The batch functions reject them (JXLR_E_PARAM). */
   int32_t  num_patches;
+  /* Dots of K.2: the number of quantized dots in io->dots (0: none), added
+   * after Gaborish (and before the noise); with dots, jxlr_finish skips its
+   * Gaborish and the caller runs jxlr_gaborish then jxlr_dots before it
+   * (jxlr_decode does).  dot_colour_quant: the draft's kColourQuant, which it
+   * does not give (finite).  The batch functions reject dots. */
+  int32_t  num_dots;
+  float    dot_colour_quant[3];
 } jxlr_frame_params;
 
 /* Input and output planes of one frame.  With Wb = ceil(xsize/8),
@@ -193,6 +200,10 @@ typedef struct {
   const int32_t* patch_place;
   const int32_t* patch_samples;
   size_t patch_samples_count;
+  /* K.2 quantized dots (C.4.5, already decoded): p->num_dots of ten int32
+   * each: x, y (times 5), sigma_x, sigma_y, angle, sign_intensity,
+   * intensity[3], is_circle. */
+  const int32_t* dots;
 } jxlr_frame_io;
 
 typedef struct jxlr_ctx jxlr_ctx;
@@ -284,14 +295,27 @@ jxlr_status jxlr_qco_pass(jxlr_ctx* ctx, const jxlr_frame_params* p, const jxlr_
 jxlr_status jxlr_patches(jxlr_ctx* ctx, const jxlr_frame_params* p, const jxlr_frame_io* io,
                          float* xyb, size_t xyb_stride, hipStream_t stream);
 
+/* J.4 alone, xyb_in -> xyb_out (distinct buffers): the Gaborish pass that
+ * precedes the dots. */
+jxlr_status jxlr_gaborish(jxlr_ctx* ctx, const jxlr_frame_params* p, const float* xyb_in,
+                          float* xyb_out, size_t xyb_stride, hipStream_t stream);
+
+/* K.2: dequantizes the dots of io (K.2.1) and adds each over its 5x5 window
+ * (samples outside the frame skipped) to the XYB planes in place (float
+ * atomics, so overlapping dots may sum in any order).  A set sign bit
+ * negates its channel's intensity. */
+jxlr_status jxlr_dots(jxlr_ctx* ctx, const jxlr_frame_params* p, const jxlr_frame_io* io,
+                      float* xyb, size_t xyb_stride, hipStream_t stream);
+
 /* K.5.2: the three pseudorandom channels of every 256x256 group of the frame
  * (frame-sized planes, float [3][ysize][xsize], row stride xsize, device
  * memory owned by the caller); they depend on the frame size only. */
 jxlr_status jxlr_noise_channels(jxlr_ctx* ctx, const jxlr_frame_params* p, float* raw,
                                 hipStream_t stream);
 
-/* Gaborish (J.4, when p->gab), noise (K.5, when p->noise, from
- * io->noise_raw) and XYB -> RGB (L.2) into io->out in p->out_format. */
+/* Gaborish (J.4, when p->gab and there are no dots), noise (K.5, when
+ * p->noise, from io->noise_raw) and XYB -> RGB (L.2) into io->out in
+ * p->out_format. */
 jxlr_status jxlr_finish(jxlr_ctx* ctx, const jxlr_frame_params* p, const jxlr_frame_io* io,
                         const float* xyb, size_t xyb_stride, hipStream_t stream);
 

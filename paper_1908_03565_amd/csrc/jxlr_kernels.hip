@@ -2057,6 +2057,86 @@ __global__ __launch_bounds__(256) void patches_kernel(PatchArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// Dots (K.2) and the Gaborish pass they need before them.  With dots the
+// finish kernel skips its Gaborish: gaborish_kernel (J.4 alone, XYB to XYB,
+// one thread per pixel) runs first, then dots_kernel, one thread per dot
+// and window sample, dequantizes its dot (K.2.1) and adds its Gaussian
+// weight times the three intensities with float atomics.
+
+struct GabArgs {
+  int W, H;
+  const float* in;
+  float* out;
+  size_t stride;
+  float k0[3], k1[3], k2[3];
+};
+
+__global__ __launch_bounds__(256) void gaborish_kernel(GabArgs a) {
+  const int x = blockIdx.x * 64 + (threadIdx.x & 63), y = blockIdx.y * 4 + (threadIdx.x >> 6);
+  if (x >= a.W || y >= a.H) return;
+  const int xl = mirror(x - 1, a.W), xr = mirror(x + 1, a.W);
+  const int yu = mirror(y - 1, a.H), yd = mirror(y + 1, a.H);
+  const size_t plane = size_t(a.H) * a.stride;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const float* p = a.in + c * plane;
+    const float* ru = p + size_t(yu) * a.stride;
+    const float* rm = p + size_t(y) * a.stride;
+    const float* rd = p + size_t(yd) * a.stride;
+    const float e4 = (ru[x] + rm[xl]) + (rm[xr] + rd[x]);
+    const float cn = (ru[xl] + ru[xr]) + (rd[xl] + rd[xr]);
+    a.out[c * plane + size_t(y) * a.stride + x] =
+        fmaf(a.k0[c], rm[x], fmaf(a.k1[c], e4, a.k2[c] * cn));
+  }
+}
+
+struct DotArgs {
+  int W, H;
+  float* xyb;
+  size_t stride;
+  const int32_t* dots;  // 10 per dot (C.4.5)
+  int n;
+  float colour_quant[3];
+};
+
+__device__ inline float lin_dequant(float x, float lo, float hi, float levels) {
+  return fmaf((hi - lo) / levels, x + 0.5f, lo);
+}
+
+__global__ __launch_bounds__(256) void dots_kernel(DotArgs a) {
+  const int t = blockIdx.x * 256 + threadIdx.x;
+  const int k = t / 25, w = t - 25 * k;
+  if (k >= a.n) return;
+  const int32_t* q = a.dots + 10 * size_t(k);
+  const float ex = float(q[0]) / 5.0f, ey = float(q[1]) / 5.0f;
+  const int ix = int(floorf(ex)) - 2 + w % 5, iy = int(floorf(ey)) - 2 + w / 5;
+  if (ix < 0 || iy < 0 || ix >= a.W || iy >= a.H) return;
+  float angle = 0.0f, sx, sy;
+  if (q[9]) {
+    sx = sy = lin_dequant(float(q[2]), 0.1f, 3.1f, 16.0f);
+  } else {
+    angle = lin_dequant(float(q[4]), 0.0f, 3.14159265358979f, 8.0f);
+    sx = lin_dequant(float(q[2]), 0.1f, 3.1f, 16.0f);
+    sy = lin_dequant(float(q[3]), 0.1f, 3.1f, 16.0f);
+  }
+  float inten[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const float v = a.colour_quant[c] * (float(q[6 + c]) + 0.5f);
+    inten[c] = (q[5] >> c) & 1 ? -v : v;
+  }
+  inten[2] = fmaf(0.935669f, inten[1], inten[2]);
+  const float ca = cosf(angle), sa = sinf(angle);
+  const float dx = float(ix) - ex, dy = float(iy) - ey;
+  const float rx = fmaf(ca, dx, sa * dy), ry = fmaf(-sa, dx, ca * dy);
+  const float md = rx * rx / (sx * sx) + ry * ry / (sy * sy);
+  const float g = expf(-0.5f * md);
+  const size_t plane = size_t(a.H) * a.stride, o = size_t(iy) * a.stride + ix;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) atomicAdd(a.xyb + c * plane + o, inten[c] * g);
+}
+
+// ---------------------------------------------------------------------------
 // Noise channels (K.5.2).  One workgroup per 256x256 group and channel; each
 // thread runs one of the eight generators over 16 rows: it seeds the
 // generator (SplitMix64 chain), jumps it ahead to its first step with the
@@ -2341,7 +2421,9 @@ jxlr_status check_params(const jxlr_frame_params* p) {
   if (p->ac_prediction < 0 || p->ac_prediction > 1 || (p->ac_prediction && !el0))
     return JXLR_E_PARAM;
   if (p->noise < 0 || p->noise > 1) return JXLR_E_PARAM;
-  if (p->num_patches < 0) return JXLR_E_PARAM;
+  if (p->num_patches < 0 || p->num_dots < 0) return JXLR_E_PARAM;
+  for (int c = 0; c < 3; ++c)
+    if (!std::isfinite(p->dot_colour_quant[c])) return JXLR_E_PARAM;
   for (int i = 0; i < 16; ++i)
     if (!std::isfinite(p->noise_lut[i])) return JXLR_E_PARAM;
   if (p->qco && (!el0 || !(p->qco_interval_mul >= 0.0f) || !std::isfinite(p->qco_interval_mul)))
@@ -2513,7 +2595,7 @@ extern "C" {
 size_t jxlr_workspace_bytes(const jxlr_frame_params* p) {
   if (check_params(p) != JXLR_OK) return 0;
   return info_bytes(p) + xyb_buffers(p) * xyb_bytes(p) + pred_bytes(p) +
-         (p->noise ? xyb_bytes(p) : 0);
+         (p->noise ? xyb_bytes(p) : 0) + (p->num_dots > 0 && p->gab ? xyb_bytes(p) : 0);
 }
 
 }  // extern "C"
@@ -2652,7 +2734,8 @@ jxlr_status make_finish_args(jxlr_ctx* ctx, const jxlr_frame_params* p, const jx
   a.H = int(p->ysize);
   a.in = xyb;
   a.stride = stride;
-  a.gab = p->gab;
+  // with dots, Gaborish runs as its own pass before them
+  a.gab = p->gab && p->num_dots == 0;
   for (int c = 0; c < 3; ++c) {
     // J.4: weights 1, w1, w2 rescaled to sum to 1
     const double w1 = p->gab_w1[c], w2 = p->gab_w2[c];
@@ -2780,6 +2863,50 @@ jxlr_status jxlr_patches(jxlr_ctx* ctx, const jxlr_frame_params* p, const jxlr_f
   return launch_status(hipGetLastError());
 }
 
+jxlr_status jxlr_gaborish(jxlr_ctx* ctx, const jxlr_frame_params* p, const float* in, float* out,
+                          size_t stride, hipStream_t stream) {
+  if (!ctx || !in || !out) return JXLR_E_NULL;
+  jxlr_status st = check_params(p);
+  if (st) return st;
+  if (stride < p->xsize) return JXLR_E_SIZE;
+  if (in == out) return JXLR_E_PARAM;
+  GabArgs a{};
+  a.W = int(p->xsize);
+  a.H = int(p->ysize);
+  a.in = in;
+  a.out = out;
+  a.stride = stride;
+  for (int c = 0; c < 3; ++c) {
+    const double w1 = p->gab_w1[c], w2 = p->gab_w2[c];
+    const double norm = 1.0 + 4.0 * w1 + 4.0 * w2;
+    a.k0[c] = float(1.0 / norm);
+    a.k1[c] = float(w1 / norm);
+    a.k2[c] = float(w2 / norm);
+  }
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return JXLR_E_HIP;
+  hipLaunchKernelGGL(gaborish_kernel, dim3((p->xsize + 63) / 64, (p->ysize + 3) / 4), dim3(256), 0,
+                     stream, a);
+  return launch_status(hipGetLastError());
+}
+
+jxlr_status jxlr_dots(jxlr_ctx* ctx, const jxlr_frame_params* p, const jxlr_frame_io* io,
+                      float* xyb, size_t stride, hipStream_t stream) {
+  if (!ctx || !io || !xyb) return JXLR_E_NULL;
+  jxlr_status st = check_params(p);
+  if (st) return st;
+  if (stride < p->xsize) return JXLR_E_SIZE;
+  if (p->num_dots == 0) return JXLR_OK;
+  if (!io->dots) return JXLR_E_NULL;
+  DotArgs a{int(p->xsize), int(p->ysize), xyb, stride, io->dots, p->num_dots, {}};
+  for (int c = 0; c < 3; ++c) a.colour_quant[c] = p->dot_colour_quant[c];
+  const long long threads = 25LL * p->num_dots;
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return JXLR_E_HIP;
+  hipLaunchKernelGGL(dots_kernel, dim3(unsigned((threads + 255) / 256)), dim3(256), 0, stream, a);
+  return launch_status(hipGetLastError());
+}
+
 jxlr_status jxlr_noise_channels(jxlr_ctx* ctx, const jxlr_frame_params* p, float* raw,
                                 hipStream_t stream) {
   if (!ctx || !raw) return JXLR_E_NULL;
@@ -2882,11 +3009,21 @@ jxlr_status jxlr_decode(jxlr_ctx* ctx, const jxlr_frame_params* p, const jxlr_fr
   }
   if (qco && (st = jxlr_qco_pass(ctx, p, io, info, buf[0], cur, stride, stream))) return st;
   if (p->num_patches > 0 && (st = jxlr_patches(ctx, p, io, cur, stride, stream))) return st;
+  char* tail = base + info_bytes(p) + xyb_buffers(p) * xyb_bytes(p) + pred_bytes(p);
   if (p->noise) {
-    float* raw = reinterpret_cast<float*>(base + info_bytes(p) + xyb_buffers(p) * xyb_bytes(p) +
-                                          pred_bytes(p));
+    float* raw = reinterpret_cast<float*>(tail);
+    tail += xyb_bytes(p);
     if ((st = jxlr_noise_channels(ctx, p, raw, stream))) return st;
     iop.noise_raw = raw;
+  }
+  if (p->num_dots > 0) {
+    // K.1: Gaborish, then the dots; the finish then skips its Gaborish
+    if (p->gab) {
+      float* gab = reinterpret_cast<float*>(tail);
+      if ((st = jxlr_gaborish(ctx, p, cur, gab, stride, stream))) return st;
+      cur = gab;
+    }
+    if ((st = jxlr_dots(ctx, p, io, cur, stride, stream))) return st;
   }
   return jxlr_finish(ctx, p, &iop, cur, stride, stream);
 }
@@ -2983,7 +3120,7 @@ size_t jxlr_batch_workspace_bytes(int n, const jxlr_frame_params* p) {
   if (n <= 0 || !p) return 0;
   for (int i = 0; i < n; ++i)
     if (check_params(&p[i]) != JXLR_OK || p[i].qco || p[i].ac_prediction || p[i].noise ||
-        p[i].num_patches)
+        p[i].num_patches || p[i].num_dots)
       return 0;
   return batch_layout(n, p).total;
 }
@@ -2996,8 +3133,9 @@ jxlr_status jxlr_batch_prepare(jxlr_ctx* ctx, int n, const jxlr_frame_params* p,
   for (int i = 0; i < n; ++i) {
     jxlr_status st = check_params(&p[i]);
     if (st) return st;
-    // the batch stages have no constraint pass, prediction, patch or noise stage
-    if (p[i].qco || p[i].ac_prediction || p[i].noise || p[i].num_patches) return JXLR_E_PARAM;
+    // the batch stages have no constraint, prediction, patch, dot or noise stage
+    if (p[i].qco || p[i].ac_prediction || p[i].noise || p[i].num_patches || p[i].num_dots)
+      return JXLR_E_PARAM;
   }
   const BatchLayout L = batch_layout(n, p);
   if (ws_bytes < L.total) return JXLR_E_WORKSPACE;

@@ -47,6 +47,8 @@ class FrameParams(C.Structure):
         ("noise", C.c_int32),
         ("noise_lut", C.c_float * 16),
         ("num_patches", C.c_int32),
+        ("num_dots", C.c_int32),
+        ("dot_colour_quant", C.c_float * 3),
     ]
 
 
@@ -62,6 +64,7 @@ class FrameIO(C.Structure):
         ("noise_raw", C.c_void_p),
         ("patch_place", C.c_void_p), ("patch_samples", C.c_void_p),
         ("patch_samples_count", C.c_size_t),
+        ("dots", C.c_void_p),
     ]
 
 
@@ -119,6 +122,10 @@ _SIGS = {
                             C.c_void_p, C.c_void_p], C.c_int),
     "jxlr_patches": ([C.c_void_p, C.POINTER(FrameParams), C.POINTER(FrameIO), C.c_void_p,
                       C.c_size_t, C.c_void_p], C.c_int),
+    "jxlr_gaborish": ([C.c_void_p, C.POINTER(FrameParams), C.c_void_p, C.c_void_p, C.c_size_t,
+                       C.c_void_p], C.c_int),
+    "jxlr_dots": ([C.c_void_p, C.POINTER(FrameParams), C.POINTER(FrameIO), C.c_void_p, C.c_size_t,
+                   C.c_void_p], C.c_int),
     "jxlr_noise_channels": ([C.c_void_p, C.POINTER(FrameParams), C.c_void_p, C.c_void_p], C.c_int),
     "jxlr_qco_pass": ([C.c_void_p, C.POINTER(FrameParams), C.POINTER(FrameIO), C.c_void_p,
                        C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p], C.c_int),
@@ -240,6 +247,8 @@ class DeviceFrame:
         self.patch_place = t(pl, np.int32) if pl is not None and len(pl) else None
         self.patch_samples = (t(frame["patch_samples"], np.int32)
                               if self.patch_place is not None else None)
+        dt = frame.get("dots")
+        self.dots = t(dt, np.int32) if dt is not None and len(dt) else None
 
     def clone(self):
         """A copy in distinct device memory."""
@@ -249,6 +258,7 @@ class DeviceFrame:
             setattr(c, k, getattr(self, k).clone())
         c.patch_place = None if self.patch_place is None else self.patch_place.clone()
         c.patch_samples = None if self.patch_samples is None else self.patch_samples.clone()
+        c.dots = None if self.dots is None else self.dots.clone()
         return c
 
     def io(self, out=None, ac_pred=None, noise_raw=None):
@@ -259,6 +269,8 @@ class DeviceFrame:
             io.patch_place = self.patch_place.data_ptr()
             io.patch_samples = self.patch_samples.data_ptr()
             io.patch_samples_count = self.patch_samples.numel()
+        if getattr(self, "dots", None) is not None:
+            io.dots = self.dots.data_ptr()
         for c in range(3):
             io.ac[c] = self.ac[c].data_ptr()
             io.dc[c] = self.dc[c].data_ptr()
@@ -355,6 +367,14 @@ class Context:
     def patches(self, p, df, xyb, stream=None):
         _check(lib().jxlr_patches(self.handle, C.byref(p), C.byref(df.io()), xyb.data_ptr(),
                                   xyb.shape[2], _stream_handle(stream)), "patches")
+
+    def gaborish(self, p, xyb_in, xyb_out, stream=None):
+        _check(lib().jxlr_gaborish(self.handle, C.byref(p), xyb_in.data_ptr(), xyb_out.data_ptr(),
+                                   xyb_in.shape[2], _stream_handle(stream)), "gaborish")
+
+    def dots(self, p, df, xyb, stream=None):
+        _check(lib().jxlr_dots(self.handle, C.byref(p), C.byref(df.io()), xyb.data_ptr(),
+                               xyb.shape[2], _stream_handle(stream)), "dots")
 
     def noise_channels(self, p, raw, stream=None):
         _check(lib().jxlr_noise_channels(self.handle, C.byref(p), raw.data_ptr(),

@@ -90,6 +90,15 @@ def gpu_stages(ctx, p, df):
             cur = xyb.clone()
         ctx.patches(p, df, cur)
         res["patches"] = cur.cpu().numpy()
+    if p.num_dots:
+        if p.gab:
+            g = ctx.empty_xyb(p)
+            ctx.gaborish(p, cur, g)
+            cur = g
+        elif cur is xyb:
+            cur = xyb.clone()
+        ctx.dots(p, df, cur)
+        res["dots"] = cur.cpu().numpy()
     out = ctx.empty_out(p)
     raw = None
     if p.noise:

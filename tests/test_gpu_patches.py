@@ -68,7 +68,8 @@ def test_patches_end_to_end(ctx, W, H, seed, n, iters):
     # jxlr_decode adds the same patches (sums of overlaps may round apart)
     out = ctx.empty_out(p)
     ctx.decode(p, df, out, ctx.workspace(p))
-    np.testing.assert_allclose(out.cpu().numpy(), gpu["out"], rtol=0, atol=1e-5)
+    # (float atomics: overlapping contributions may sum in another order)
+    np.testing.assert_allclose(out.cpu().numpy(), gpu["out"], rtol=2e-6, atol=1e-5)
 
 
 def test_ill_formed_patch_sets_the_flag(ctx):

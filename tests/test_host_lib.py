@@ -41,8 +41,8 @@ def test_defaults_agree_with_oracle():
     q = O.params(64, 48)
     for name, _ in J.FrameParams._fields_:
         # output format and transform arithmetic are the library's own; the
-        # patch count travels with the patch arrays on the oracle's side
-        if name in ("out_format", "idct_split", "num_patches"):
+        # patch and dot counts travel with their arrays on the oracle's side
+        if name in ("out_format", "idct_split", "num_patches", "num_dots"):
             continue
         a, b = getattr(p, name), getattr(q, name)
         if isinstance(a, C.Array):
@@ -115,8 +115,9 @@ def test_parameter_ranges():
         assert J.validate_maps_host(p, f) == 7
         assert J.workspace_bytes(p) == 0
     assert J.params(64, 64).noise == 0
-    p = J.params(64, 64, num_patches=-1)
-    assert J.validate_maps_host(p, f) == 7 and J.workspace_bytes(p) == 0
+    for kw in (dict(num_patches=-1), dict(num_dots=-2), dict(dot_colour_quant=(0, float("inf"), 0))):
+        p = J.params(64, 64, **kw)
+        assert J.validate_maps_host(p, f) == 7 and J.workspace_bytes(p) == 0, kw
     d = J.params(64, 64)
     assert d.qco == 0 and d.qco_interval_mul == 0.5  # C.10 defaults
 
@@ -157,6 +158,7 @@ def test_batch_workspace_bytes():
     assert J.batch_workspace_bytes(ps + [J.params(64, 64, ac_prediction=1)]) == 0
     assert J.batch_workspace_bytes(ps + [J.params(64, 64, noise=1)]) == 0
     assert J.batch_workspace_bytes(ps + [J.params(64, 64, num_patches=3)]) == 0
+    assert J.batch_workspace_bytes(ps + [J.params(64, 64, num_dots=3)]) == 0
 
 
 # --- the library's constant tables versus the oracle's --------------------
