@@ -2108,9 +2108,15 @@ __global__ __launch_bounds__(256) void dots_kernel(DotArgs a) {
   const int k = t / 25, w = t - 25 * k;
   if (k >= a.n) return;
   const int32_t* q = a.dots + 10 * size_t(k);
-  const float ex = float(q[0]) / 5.0f, ey = float(q[1]) / 5.0f;
-  const int ix = int(floorf(ex)) - 2 + w % 5, iy = int(floorf(ey)) - 2 + w / 5;
-  if (ix < 0 || iy < 0 || ix >= a.W || iy >= a.H) return;
+  // the centre is (q[0], q[1]) / 5: the window's corner and each sample's
+  // offset from the centre come from exact integers (a binary32 centre far
+  // from the origin would be off by up to half an ulp of the coordinate)
+  const long long qx = q[0], qy = q[1];
+  const long long fx = qx >= 0 ? qx / 5 : -((4 - qx) / 5);
+  const long long fy = qy >= 0 ? qy / 5 : -((4 - qy) / 5);
+  const long long jx = fx - 2 + w % 5, jy = fy - 2 + w / 5;
+  if (jx < 0 || jy < 0 || jx >= a.W || jy >= a.H) return;
+  const int ix = int(jx), iy = int(jy);
   float angle = 0.0f, sx, sy;
   if (q[9]) {
     sx = sy = lin_dequant(float(q[2]), 0.1f, 3.1f, 16.0f);
@@ -2127,7 +2133,7 @@ __global__ __launch_bounds__(256) void dots_kernel(DotArgs a) {
   }
   inten[2] = fmaf(0.935669f, inten[1], inten[2]);
   const float ca = cosf(angle), sa = sinf(angle);
-  const float dx = float(ix) - ex, dy = float(iy) - ey;
+  const float dx = float(5 * jx - qx) / 5.0f, dy = float(5 * jy - qy) / 5.0f;
   const float rx = fmaf(ca, dx, sa * dy), ry = fmaf(-sa, dx, ca * dy);
   const float md = rx * rx / (sx * sx) + ry * ry / (sy * sy);
   const float g = expf(-0.5f * md);
