@@ -69,22 +69,22 @@ def log(msg):
 PMC_COPY_SCALE = {"FETCH_SIZE": 2.0, "WRITE_SIZE": 1.0}
 PMC_SOURCES = ("paper_1908_03565_amd/csrc/jxlr_kernels.hip", "paper_1908_03565_amd/csrc/jxlr_tables.cpp",
                "paper_1908_03565_amd/csrc/jxlr_tables.h", "paper_1908_03565_amd/csrc/gen_dct_consts.py")
-PMC_SOURCES_SHA256 = "98f5a478c42ce531bfd446b6d0411c159851b2e0b14b28f7ad6c891d20542631"
+PMC_SOURCES_SHA256 = "91327227f92f4aea1ae7e20081335115f9465b23c55b13716ef1d79a4503a199"
 # (workload name, kernel) -> (FETCH_SIZE KiB, WRITE_SIZE KiB) per dispatch
 PMC_KIB = {
-    ("c2_2048x2048_mixed_epf2", "epf_kernel"): (25442.3, 49152.0),
-    ("c2_2048x2048_mixed_epf2", "recon_kernel"): (25809.6, 49481.8),
-    ("c2_2048x2048_mixed_epf2", "finish_kernel"): (24911.6, 49152.0),
-    ("c2_2048x2048_mixed_epf2_qco", "epf_kernel"): (25442.6, 49152.0),
-    ("c2_2048x2048_mixed_epf2_qco", "qco_kernel"): (70870.1, 49152.0),
-    ("c3_4096x4096_half_dct32", "epf_kernel"): (101209.5, 196608.0),
-    ("c3_4096x4096_half_dct32", "recon_kernel"): (101298.4, 197253.3),
-    ("c3_4096x4096_half_dct32", "finish_kernel"): (98879.1, 196608.0),
-    ("c4_batch64_loguniform_256_3072_epf1_u8srgb", "epf_batch_kernel"): (528700.8, 1052239.1),
-    ("c4_batch64_loguniform_256_3072_epf1_u8srgb", "recon_batch_kernel"): (536210.5, 1058835.2),
-    ("c4_batch64_loguniform_256_3072_epf1_u8srgb", "finish_batch_kernel"): (526386.1, 263633.6),
-    ("c1x1024_256x256_dct8", "recon_batch_kernel"): (401019.3, 786434.0),
-    ("c1x1024_256x256_dct8", "finish_batch_kernel"): (845306.3, 786432.0),
+    ("c2_2048x2048_mixed_epf2", "epf_kernel"): (25439.5, 49152.0),
+    ("c2_2048x2048_mixed_epf2", "recon_kernel"): (25790.4, 49481.2),
+    ("c2_2048x2048_mixed_epf2", "finish_kernel"): (24909.4, 49152.0),
+    ("c2_2048x2048_mixed_epf2_qco", "epf_kernel"): (25439.8, 49152.0),
+    ("c2_2048x2048_mixed_epf2_qco", "qco_kernel"): (70843.6, 49152.0),
+    ("c3_4096x4096_half_dct32", "epf_kernel"): (101707.3, 196608.1),
+    ("c3_4096x4096_half_dct32", "recon_kernel"): (101290.8, 197288.5),
+    ("c3_4096x4096_half_dct32", "finish_kernel"): (100388.8, 196608.0),
+    ("c4_batch64_loguniform_256_3072_epf1_u8srgb", "epf_batch_kernel"): (528688.8, 1052226.1),
+    ("c4_batch64_loguniform_256_3072_epf1_u8srgb", "recon_batch_kernel"): (536182.0, 1058003.7),
+    ("c4_batch64_loguniform_256_3072_epf1_u8srgb", "finish_batch_kernel"): (526415.0, 263651.9),
+    ("c1x1024_256x256_dct8", "recon_batch_kernel"): (401020.2, 786433.0),
+    ("c1x1024_256x256_dct8", "finish_batch_kernel"): (430138.1, 786432.0),
 }
 
 
