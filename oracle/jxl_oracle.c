@@ -1594,6 +1594,206 @@ int orc_dots(const orc_params* p, const int32_t* dots, int32_t n, double* xyb) {
 }
 
 /* ======================================================================= */
+/* Splines (K.4)                                                           */
+/* ======================================================================= */
+
+/* K.4 ContinuousIDCT of one channel's 32 coefficients at t: DCTScale(k) is
+ * D(32, k) of I.2.6.1 times 1/(4 sqrt 2) for k = 0, times 1/4 otherwise. */
+double orc_spline_idct(const float* dct, double t) {
+  const double kPi = 3.14159265358979323846;
+  double s = 0.0;
+  for (int k = 0; k < 32; ++k) {
+    const double scale = orc_scale_D(32, k) * (k == 0 ? 1.0 / (4.0 * sqrt(2.0)) : 0.25);
+    s += scale * dct[k] * cos(k * (kPi / 32.0) * (t + 0.5));
+  }
+  return s;
+}
+
+/* K.4 step 1: the sequence C sampling the centripetal Catmull-Rom curve
+ * through the n control points pts[2n] (x, y): one control point alone, else
+ * the control points extended by a mirrored point at each end, and for every
+ * window of four consecutive points its second point followed by the curve
+ * at 15 parameters strictly between the second and third (steps of one 16th
+ * of that parameter interval), then the last control point.  cx, cy: room
+ * for 16 (n - 1) + 1 points.  Returns the number of points, or -1 when two
+ * consecutive control points coincide (a zero parameter interval). */
+int32_t orc_spline_curve(const int32_t* pts, int32_t n, double* cx, double* cy) {
+  if (n < 1) return -1;
+  cx[0] = pts[0];
+  cy[0] = pts[1];
+  if (n == 1) return 1;
+  for (int32_t i = 0; i + 1 < n; ++i)
+    if (pts[2 * i] == pts[2 * i + 2] && pts[2 * i + 1] == pts[2 * i + 3]) return -1;
+  /* E: Mirror(first, second), the control points, Mirror(last, second-to-last) */
+  double* ex = (double*)malloc(sizeof(double) * (n + 2));
+  double* ey = (double*)malloc(sizeof(double) * (n + 2));
+  if (!ex || !ey) { free(ex); free(ey); return -1; }
+  ex[0] = 2.0 * pts[0] - pts[2];
+  ey[0] = 2.0 * pts[1] - pts[3];
+  for (int32_t i = 0; i < n; ++i) { ex[i + 1] = pts[2 * i]; ey[i + 1] = pts[2 * i + 1]; }
+  ex[n + 1] = 2.0 * pts[2 * n - 2] - pts[2 * n - 4];
+  ey[n + 1] = 2.0 * pts[2 * n - 1] - pts[2 * n - 3];
+  int32_t m = 0;
+  for (int32_t w = 0; w + 3 < n + 2; ++w) {
+    const double* px = ex + w;
+    const double* py = ey + w;
+    cx[m] = px[1];
+    cy[m] = py[1];
+    ++m;
+    double tk[4];
+    tk[0] = 0.0;
+    for (int k = 1; k < 4; ++k) {
+      const double dx = px[k] - px[k - 1], dy = py[k] - py[k - 1];
+      tk[k] = tk[k - 1] + pow(dx * dx + dy * dy, 0.25);
+    }
+    for (int step = 1; step < 16; ++step) {
+      const double t = tk[1] + step * (tk[2] - tk[1]) / 16.0;
+      double ax[3], ay[3], bx[2], by[2];
+      for (int k = 0; k < 3; ++k) {
+        const double f = (t - tk[k]) / (tk[k + 1] - tk[k]);
+        ax[k] = px[k] + f * (px[k + 1] - px[k]);
+        ay[k] = py[k] + f * (py[k + 1] - py[k]);
+      }
+      for (int k = 0; k < 2; ++k) {
+        const double f = (t - tk[k]) / (tk[k + 2] - tk[k]);
+        bx[k] = ax[k] + f * (ax[k + 1] - ax[k]);
+        by[k] = ay[k] + f * (ay[k + 1] - ay[k]);
+      }
+      const double f = (t - tk[1]) / (tk[2] - tk[1]);
+      cx[m] = bx[0] + f * (bx[1] - bx[0]);
+      cy[m] = by[0] + f * (by[1] - by[0]);
+      ++m;
+    }
+  }
+  cx[m] = ex[n];
+  cy[m] = ey[n];
+  ++m;
+  free(ex);
+  free(ey);
+  return m;
+}
+
+/* K.4 step 2 to 3: the points P along the polyline through C (m points) at
+ * arc lengths 0, 1, 2, ..., then the last point of C if the walk did not end
+ * on it.  Writes up to cap points (x, y, arc position l, distance d from the
+ * previous point, 1 for the first) and returns their number; *L_out: the
+ * polyline's length.  Zero-length pieces of the polyline are passed over. */
+int32_t orc_spline_walk(const double* cx, const double* cy, int32_t m, double* P, int32_t cap,
+                        double* L_out) {
+  double L = 0.0;
+  for (int32_t i = 0; i + 1 < m; ++i) L += hypot(cx[i + 1] - cx[i], cy[i + 1] - cy[i]);
+  *L_out = L;
+  int32_t np = 0;
+  if (np < cap) { P[0] = cx[0]; P[1] = cy[0]; P[2] = 0.0; P[3] = 1.0; }
+  np = 1;
+  double next = 1.0, arc = 0.0;
+  for (int32_t i = 0; i + 1 < m; ++i) {
+    const double len = hypot(cx[i + 1] - cx[i], cy[i + 1] - cy[i]);
+    if (len == 0.0) continue;
+    while (next <= arc + len) {
+      const double f = (next - arc) / len;
+      if (np < cap) {
+        double* q = P + 4 * np;
+        q[0] = cx[i] + f * (cx[i + 1] - cx[i]);
+        q[1] = cy[i] + f * (cy[i + 1] - cy[i]);
+        q[2] = next;
+        q[3] = 1.0;
+      }
+      ++np;
+      next += 1.0;
+    }
+    arc += len;
+  }
+  /* the last element of C unless the walk ended exactly on it */
+  const double last = next - 1.0;
+  if (m > 1 && last < L) {
+    if (np < cap) {
+      double* q = P + 4 * np;
+      q[0] = cx[m - 1];
+      q[1] = cy[m - 1];
+      q[2] = L;
+      q[3] = L - last;
+    }
+    ++np;
+  }
+  return np;
+}
+
+/* K.4: n splines added in place after the dots.  offsets[n + 1]: the
+ * control points of spline s are pts[2 offsets[s] .. 2 offsets[s + 1]), as
+ * (x, y); dct[n][4][32]: the dequantized and recorrelated DCT32 coefficients
+ * of X, Y, B and sigma along the arc length.  Each point p of P (position l,
+ * distance d) takes value = ContinuousIDCT(dct, 31 l / L) per channel and
+ * adds, to every pixel (x, y) of the frame whose squared distance from p is
+ * at most -2 sigma^2 log(0.1), value d sigma / 4 times the product of the
+ * two differences of erf over the pixel's extent [x - 0.5, x + 0.5] (and the
+ * same in y), each divided by sqrt(2) sigma.  Readings: "within r of p"
+ * compares the squared distance with r (the Gaussian's tenth-of-peak
+ * contour); steps of exactly one 16th of the parameter interval; a spline of
+ * zero length (one control point) evaluates its values at t = 0; a point
+ * whose sigma is not positive adds nothing.  near (may be NULL): [H][W],
+ * set where a point's squared distance lies within 1e-9 of that bound,
+ * relative (binary64 rounding can decide those pixels either way).  Returns
+ * ORC_E_PARAM if a spline has no control points or two consecutive equal
+ * ones. */
+int orc_splines(const orc_params* p, const int32_t* offsets, int32_t n, const int32_t* pts,
+                const float* dct, double* xyb, uint8_t* near) {
+  const int32_t W = p->xsize, H = p->ysize;
+  const size_t plane = (size_t)W * H;
+  const double kLog01 = log(0.1);
+  for (int32_t s = 0; s < n; ++s) {
+    const int32_t nc = offsets[s + 1] - offsets[s];
+    if (nc < 1) return ORC_E_PARAM;
+    for (int32_t i = 0; i + 1 < nc; ++i) {
+      const int32_t* q = pts + 2 * (offsets[s] + i);
+      if (q[0] == q[2] && q[1] == q[3]) return ORC_E_PARAM;
+    }
+  }
+  for (int32_t s = 0; s < n; ++s) {
+    const int32_t nc = offsets[s + 1] - offsets[s];
+    const int32_t cap_c = 16 * (nc - 1) + 1;
+    double* cx = (double*)malloc(sizeof(double) * cap_c);
+    double* cy = (double*)malloc(sizeof(double) * cap_c);
+    if (!cx || !cy) { free(cx); free(cy); return ORC_E_SIZE; }
+    const int32_t m = orc_spline_curve(pts + 2 * offsets[s], nc, cx, cy);
+    double L;
+    const int32_t np = orc_spline_walk(cx, cy, m, NULL, 0, &L);
+    double* P = (double*)malloc(sizeof(double) * 4 * np);
+    if (!P) { free(cx); free(cy); return ORC_E_SIZE; }
+    orc_spline_walk(cx, cy, m, P, np, &L);
+    const float* sd = dct + (size_t)s * 128;
+    for (int32_t j = 0; j < np; ++j) {
+      const double px = P[4 * j], py = P[4 * j + 1], l = P[4 * j + 2], d = P[4 * j + 3];
+      const double t = L > 0.0 ? 31.0 * l / L : 0.0;
+      double v[3];
+      for (int c = 0; c < 3; ++c) v[c] = orc_spline_idct(sd + 32 * c, t);
+      const double sigma = orc_spline_idct(sd + 96, t);
+      if (!(sigma > 0.0)) continue;
+      const double r2 = -2.0 * sigma * sigma * kLog01;
+      const double r = sqrt(r2);
+      const double s2s = sqrt(2.0) * sigma;
+      const int32_t x0 = (int32_t)fmax(0.0, floor(px - r)), x1 = (int32_t)fmin(W - 1.0, ceil(px + r));
+      const int32_t y0 = (int32_t)fmax(0.0, floor(py - r)), y1 = (int32_t)fmin(H - 1.0, ceil(py + r));
+      for (int32_t y = y0; y <= y1; ++y)
+        for (int32_t x = x0; x <= x1; ++x) {
+          const double dx = px - x, dy = py - y;
+          const double dd = dx * dx + dy * dy;
+          if (near && fabs(dd - r2) <= 1e-9 * r2) near[(size_t)y * W + x] = 1;
+          if (dd > r2) continue;
+          const double g = (erf((dx + 0.5) / s2s) - erf((dx - 0.5) / s2s)) *
+                           (erf((dy + 0.5) / s2s) - erf((dy - 0.5) / s2s));
+          for (int c = 0; c < 3; ++c)
+            xyb[c * plane + (size_t)y * W + x] += v[c] * d * sigma / 4.0 * g;
+        }
+    }
+    free(P);
+    free(cx);
+    free(cy);
+  }
+  return ORC_OK;
+}
+
+/* ======================================================================= */
 /* Noise (K.5)                                                             */
 /* ======================================================================= */
 
@@ -1794,7 +1994,7 @@ int orc_decode(const orc_params* p, const int32_t* const ac[3], const int32_t* c
                const uint8_t* strategy, const uint8_t* qf_minus_1, const uint8_t* sharpness,
                const float* cfl_kx, const float* cfl_kb, double* rgb) {
   return orc_decode_features(p, ac, dc, strategy, qf_minus_1, sharpness, cfl_kx, cfl_kb, NULL, 0,
-                             NULL, NULL, 0, rgb);
+                             NULL, NULL, 0, NULL, 0, NULL, NULL, rgb);
 }
 
 int orc_decode_features(const orc_params* p, const int32_t* const ac[3],
@@ -1802,7 +2002,8 @@ int orc_decode_features(const orc_params* p, const int32_t* const ac[3],
                         const uint8_t* qf_minus_1, const uint8_t* sharpness, const float* cfl_kx,
                         const float* cfl_kb, const int32_t* patch_place, int32_t n_patches,
                         const int32_t* patch_samples, const int32_t* dots, int32_t n_dots,
-                        double* rgb) {
+                        const int32_t* spline_offsets, int32_t n_splines,
+                        const int32_t* spline_points, const float* spline_dct, double* rgb) {
   int st = check_params(p);
   if (st) return st;
   const size_t n = 3 * (size_t)p->xsize * p->ysize;
@@ -1834,6 +2035,9 @@ int orc_decode_features(const orc_params* p, const int32_t* const ac[3],
   }
   /* K.1: dots, then noise, after Gaborish */
   if (!st && n_dots > 0) st = orc_dots(p, dots, n_dots, a);
+  /* K.4: splines after the dots */
+  if (!st && n_splines > 0)
+    st = orc_splines(p, spline_offsets, n_splines, spline_points, spline_dct, a, NULL);
   if (!st && p->noise) {
     st = orc_noise(p, a, b);
     double* t = a; a = b; b = t;

@@ -156,6 +156,18 @@ int orc_patches(const orc_params* p, const int32_t* place, int32_t n, const int3
 /* K.2 dots, added in place: n quantized dots of 10 integers (x, y, sigma_x,
  * sigma_y, angle, sign_intensity, intensity[3], is_circle). */
 int orc_dots(const orc_params* p, const int32_t* dots, int32_t n, double* xyb);
+/* K.4 splines, added in place: ContinuousIDCT of 32 coefficients at t; the
+ * sampled centripetal Catmull-Rom sequence C of n control points (room for
+ * 16 (n - 1) + 1; -1 if consecutive points coincide); the unit-arc-length
+ * walk P over C (x, y, l, d per point; returns the count, *L the length);
+ * and the rendering of n splines (offsets[n + 1] into pts (x, y) pairs,
+ * dct[n][4][32] for X, Y, B, sigma; near: [H][W] flags or NULL). */
+double orc_spline_idct(const float* dct, double t);
+int32_t orc_spline_curve(const int32_t* pts, int32_t n, double* cx, double* cy);
+int32_t orc_spline_walk(const double* cx, const double* cy, int32_t m, double* P, int32_t cap,
+                        double* L);
+int orc_splines(const orc_params* p, const int32_t* offsets, int32_t n, const int32_t* pts,
+                const float* dct, double* xyb, uint8_t* near);
 /* K.5.2 SplitMix64 and the three pseudorandom channels [3][gh][gw] of the
  * group with top-left pixel (x0, y0). */
 uint64_t orc_splitmix64(uint64_t z);
@@ -184,14 +196,15 @@ int orc_decode(const orc_params* p,
                double* rgb);
 
 /* The same with patches (K.3) between the filters and Gaborish, and dots
- * (K.2) between Gaborish and the noise. */
+ * (K.2) then splines (K.4) between Gaborish and the noise. */
 int orc_decode_features(const orc_params* p,
                         const int32_t* const ac[3], const int32_t* const dc[3],
                         const uint8_t* strategy, const uint8_t* qf_minus_1,
                         const uint8_t* sharpness, const float* cfl_kx, const float* cfl_kb,
                         const int32_t* patch_place, int32_t n_patches,
                         const int32_t* patch_samples, const int32_t* dots, int32_t n_dots,
-                        double* rgb);
+                        const int32_t* spline_offsets, int32_t n_splines,
+                        const int32_t* spline_points, const float* spline_dct, double* rgb);
 /* Number of OpenMP threads the oracle runs with (1 when built without OpenMP). */
 int orc_num_threads(void);
 

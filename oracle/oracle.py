@@ -93,8 +93,17 @@ def lib():
         L.orc_patches.argtypes = [P, _i32p, C.c_int32, _i32p, _f64p]
         L.orc_decode_features.argtypes = [P, ptr3, ptr3, _u8p, _u8p, _u8p, _f32p, _f32p,
                                           C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p,
-                                          C.c_int32, _f64p]
+                                          C.c_int32, C.c_void_p, C.c_int32, C.c_void_p,
+                                          C.c_void_p, _f64p]
         L.orc_dots.argtypes = [P, _i32p, C.c_int32, _f64p]
+        L.orc_spline_idct.argtypes = [_f32p, C.c_double]
+        L.orc_spline_idct.restype = C.c_double
+        L.orc_spline_curve.argtypes = [_i32p, C.c_int32, _f64p, _f64p]
+        L.orc_spline_curve.restype = C.c_int32
+        L.orc_spline_walk.argtypes = [_f64p, _f64p, C.c_int32, C.c_void_p, C.c_int32,
+                                      C.POINTER(C.c_double)]
+        L.orc_spline_walk.restype = C.c_int32
+        L.orc_splines.argtypes = [P, _i32p, C.c_int32, _i32p, _f32p, _f64p, C.c_void_p]
         L.orc_xyb_to_rgb.argtypes = [P, _f64p, _f64p]
         L.orc_quantize_srgb.argtypes = [C.c_int32, C.c_int64, _f64p, _u16p]
         L.orc_decode.argtypes = [P, ptr3, ptr3, _u8p, _u8p, _u8p, _f32p, _f32p, _f64p]
@@ -342,6 +351,51 @@ def dots(p, quantized, xyb):
     return out
 
 
+def spline_idct(dct, t):
+    """K.4 ContinuousIDCT of 32 coefficients at t."""
+    return lib().orc_spline_idct(np.ascontiguousarray(dct, np.float32).ravel(), float(t))
+
+
+def spline_curve(points):
+    """K.4 step 1: the sequence C (m, 2) of the centripetal Catmull-Rom
+    curve through the control points (n, 2); None if two consecutive control
+    points coincide."""
+    pts = np.ascontiguousarray(points, np.int32).reshape(-1, 2)
+    n = len(pts)
+    cap = 16 * (n - 1) + 1
+    cx, cy = np.zeros(cap), np.zeros(cap)
+    m = lib().orc_spline_curve(pts.ravel(), n, cx, cy)
+    return None if m < 0 else np.stack([cx[:m], cy[:m]], axis=1)
+
+
+def spline_walk(curve):
+    """K.4 steps 2-3: the points P (np, 4) of (x, y, l, d) at unit arc
+    length along the polyline through C, and its length L."""
+    c = np.ascontiguousarray(curve, np.float64).reshape(-1, 2)
+    cx, cy = np.ascontiguousarray(c[:, 0]), np.ascontiguousarray(c[:, 1])
+    L = C.c_double()
+    n = lib().orc_spline_walk(cx, cy, len(c), None, 0, C.byref(L))
+    P = np.zeros((n, 4))
+    lib().orc_spline_walk(cx, cy, len(c), P.ctypes.data, n, C.byref(L))
+    return P, L.value
+
+
+def splines(p, offsets, points, dct, xyb, want_near=False):
+    """K.4: splines added to a copy of the image.  offsets (n + 1,), points
+    (m, 2) int32, dct (n, 4, 32) float32.  With want_near, also the [H][W]
+    mask of pixels whose footprint test is within 1e-9 of its bound."""
+    out = np.array(xyb, dtype=np.float64, order="C", copy=True)
+    off = np.ascontiguousarray(offsets, np.int32).ravel()
+    pts = np.ascontiguousarray(points, np.int32).reshape(-1, 2)
+    d = np.ascontiguousarray(dct, np.float32).reshape(-1, 4, 32)
+    near = np.zeros((p.ysize, p.xsize), np.uint8)
+    _check(lib().orc_splines(C.byref(p), off, len(off) - 1,
+                             pts.ravel() if pts.size else np.zeros(2, np.int32),
+                             d.ravel() if d.size else np.zeros(128, np.float32), out,
+                             near.ctypes.data))
+    return (out, near.astype(bool)) if want_near else out
+
+
 def splitmix64(z):
     return lib().orc_splitmix64(int(z) & (2**64 - 1))
 
@@ -384,7 +438,9 @@ def quantize_srgb(bits, lin):
 
 def decode(p, frame):
     """Whole path: returns [0,1]-scaled linear RGB (3, ysize, xsize) float64.
-    Patches (K.3) come from frame["patch_place"] / frame["patch_samples"]."""
+    Patches (K.3) come from frame["patch_place"] / frame["patch_samples"],
+    dots (K.2) from frame["dots"], splines (K.4) from frame["spline_offsets"]
+    / frame["spline_points"] / frame["spline_dct"]."""
     ka, pa = _planes(frame["ac"], np.int32)
     kd, pd = _planes(frame["dc"], np.int32)
     out = np.zeros((3, p.ysize, p.xsize))
@@ -395,6 +451,11 @@ def decode(p, frame):
     dt = frame.get("dots")
     nd = 0 if dt is None else len(dt)
     dt = np.ascontiguousarray(dt, np.int32) if nd else None
+    so = frame.get("spline_offsets")
+    ns = 0 if so is None else len(so) - 1
+    so = np.ascontiguousarray(so, np.int32) if ns else None
+    sp = np.ascontiguousarray(frame["spline_points"], np.int32) if ns else None
+    sd = np.ascontiguousarray(frame["spline_dct"], np.float32) if ns else None
     _check(lib().orc_decode_features(
         C.byref(p), pa, pd, np.ascontiguousarray(frame["strategy"], np.uint8),
         np.ascontiguousarray(frame["qf"], np.uint8),
@@ -402,7 +463,8 @@ def decode(p, frame):
         np.ascontiguousarray(frame["cfl_kx"], np.float32),
         np.ascontiguousarray(frame["cfl_kb"], np.float32),
         pl.ctypes.data if n else None, n, sm.ctypes.data if n else None,
-        dt.ctypes.data if nd else None, nd, out))
+        dt.ctypes.data if nd else None, nd, so.ctypes.data if ns else None, ns,
+        sp.ctypes.data if ns else None, sd.ctypes.data if ns else None, out))
     return out
 
 
@@ -428,6 +490,9 @@ def decode_stages(p, frame):
     if frame.get("dots") is not None and len(frame["dots"]):
         cur = dots(p, frame["dots"], cur)
         res["dots"] = cur
+    if frame.get("spline_offsets") is not None and len(frame["spline_offsets"]) > 1:
+        cur = splines(p, frame["spline_offsets"], frame["spline_points"], frame["spline_dct"], cur)
+        res["splines"] = cur
     if p.noise:
         cur = noise(p, cur)
         res["noise"] = cur

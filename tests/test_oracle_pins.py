@@ -1024,6 +1024,185 @@ def test_dots_follow_gaborish_and_precede_noise():
 
 
 # --------------------------------------------------------------------------
+# Splines (K.4)
+# --------------------------------------------------------------------------
+
+def _dct_scale32(k):
+    # I.2.6.1: D(32, k) = sqrt(2 / 32) eps cos(k pi / 64), eps = sqrt(1/2) at 0;
+    # K.4 multiplies by 1 / (4 sqrt 2) at k = 0 and by 1/4 elsewhere
+    return 1.0 / 32.0 if k == 0 else math.cos(k * math.pi / 64.0) / 16.0
+
+
+def test_spline_idct_is_a_dct3_at_integer_and_quarter_points():
+    import scipy.fft as sf
+    c = _rng(150).standard_normal(32).astype(np.float32)
+    # sum_k s_k c_k cos(k pi (t + 1/2) / 32) is scipy's unnormalized DCT-III
+    # (x0 + 2 sum x_k cos(pi k (2j + 1) / 2N)) of x_0 = s_0 c_0, x_k = s_k c_k / 2
+    x = np.array([_dct_scale32(k) * float(c[k]) * (1.0 if k == 0 else 0.5) for k in range(32)])
+    want = sf.dct(x, type=3)
+    got = [O.spline_idct(c, t) for t in range(32)]
+    np.testing.assert_allclose(got, want, rtol=0, atol=1e-13)
+    # zero-padded to 64 points: t + 1/2 = (2j + 1) / 4, i.e. t = (2j - 1) / 4
+    want64 = sf.dct(np.concatenate([x, np.zeros(32)]), type=3)
+    got64 = [O.spline_idct(c, (2 * j - 1) / 4.0) for j in range(64)]
+    np.testing.assert_allclose(got64, want64, rtol=0, atol=1e-13)
+    one = np.zeros(32, np.float32)
+    one[0] = 64.0
+    assert O.spline_idct(one, 12.3) == pytest.approx(2.0, rel=1e-15)
+
+
+def test_spline_curve_on_a_uniform_line_is_uniform():
+    # collinear, equally spaced control points: the centripetal curve is the
+    # line itself at a uniform parameter (every knot interval is equal)
+    pts = np.array([[3, 5], [11, 11], [19, 17], [27, 23]])
+    c = O.spline_curve(pts)
+    assert c.shape == (16 * 3 + 1, 2)
+    u = np.arange(49) / 16.0
+    np.testing.assert_allclose(c, pts[0] + u[:, None] * (pts[1] - pts[0]), atol=1e-12)
+    np.testing.assert_array_equal(c[::16], pts)
+
+
+def _hermite_centripetal(e, n_sub=16):
+    # the cubic Hermite form of one centripetal Catmull-Rom segment p1 -> p2
+    # (equivalent to the Barry-Goldman pyramid the draft evaluates), with the
+    # tangents of Yuksel, Schaefer and Keyser (2011)
+    p0, p1, p2, p3 = (np.asarray(v, float) for v in e)
+    t0 = 0.0
+    t1 = t0 + np.linalg.norm(p1 - p0) ** 0.5
+    t2 = t1 + np.linalg.norm(p2 - p1) ** 0.5
+    t3 = t2 + np.linalg.norm(p3 - p2) ** 0.5
+    m1 = (t2 - t1) * ((p1 - p0) / (t1 - t0) - (p2 - p0) / (t2 - t0) + (p2 - p1) / (t2 - t1))
+    m2 = (t2 - t1) * ((p2 - p1) / (t2 - t1) - (p3 - p1) / (t3 - t1) + (p3 - p2) / (t3 - t2))
+    out = []
+    for k in range(n_sub):
+        u = k / n_sub
+        h00, h10 = 2 * u ** 3 - 3 * u ** 2 + 1, u ** 3 - 2 * u ** 2 + u
+        h01, h11 = -2 * u ** 3 + 3 * u ** 2, u ** 3 - u ** 2
+        out.append(h00 * p1 + h10 * m1 + h01 * p2 + h11 * m2)
+    return np.array(out)
+
+
+@pytest.mark.parametrize("n", [2, 3, 7])
+def test_spline_curve_matches_the_hermite_form(n):
+    rng = _rng(151 + n)
+    pts = rng.integers(-40, 200, size=(n, 2))
+    while np.any(np.all(pts[1:] == pts[:-1], axis=1)):
+        pts = rng.integers(-40, 200, size=(n, 2))
+    c = O.spline_curve(pts)
+    e = np.concatenate([[2 * pts[0] - pts[1]], pts, [2 * pts[-1] - pts[-2]]]).astype(float)
+    want = np.concatenate([_hermite_centripetal(e[w:w + 4]) for w in range(n - 1)] + [pts[-1:]])
+    np.testing.assert_allclose(c, want, rtol=0, atol=1e-9)
+
+
+def test_spline_curve_single_point_and_coincident_points():
+    np.testing.assert_array_equal(O.spline_curve([[7, -3]]), [[7.0, -3.0]])
+    assert O.spline_curve([[1, 2], [5, 6], [5, 6]]) is None
+
+
+@pytest.mark.parametrize("pts", [[[0, 0], [37, 0]], [[5, 9], [30, 40], [61, 12], [80, 77]],
+                                 [[0, 0], [3, 4]]])
+def test_spline_walk_is_unit_arc_length_along_the_polyline(pts):
+    c = O.spline_curve(pts)
+    P, L = O.spline_walk(c)
+    seg = np.hypot(*np.diff(c, axis=0).T)
+    arc = np.concatenate([[0.0], np.cumsum(seg)])
+    assert L == pytest.approx(arc[-1], rel=1e-14)
+    n_int = int(math.floor(L)) + 1
+    frac = L - math.floor(L)
+    assert len(P) == n_int + (frac > 1e-12)
+    np.testing.assert_allclose(P[:n_int, 2], np.arange(n_int))
+    # positions by interpolation along the cumulative arc length
+    np.testing.assert_allclose(P[:, 0], np.interp(P[:, 2], arc, c[:, 0]), atol=1e-9)
+    np.testing.assert_allclose(P[:, 1], np.interp(P[:, 2], arc, c[:, 1]), atol=1e-9)
+    np.testing.assert_array_equal(P[:n_int, 3], 1.0)
+    if frac > 1e-12:
+        np.testing.assert_allclose(P[-1], [c[-1, 0], c[-1, 1], L, frac], atol=1e-9)
+
+
+def _spline_dct(values, sigma):
+    # constant X, Y, B and sigma along the spline: dct[0] = 32 v
+    d = np.zeros((4, 32), np.float32)
+    d[:3, 0] = 32.0 * np.asarray(values)
+    d[3, 0] = 32.0 * sigma
+    return d
+
+
+def test_spline_single_point_footprint_is_the_pixel_integral_of_a_gaussian():
+    from scipy import integrate
+    W, H = 40, 32
+    p = O.params(W, H)
+    sig, v = 2.25, (0.5, -1.0, 2.0)
+    out = O.splines(p, [0, 1], [[17, 12]], _spline_dct(v, sig)[None], np.zeros((3, H, W)))
+    r2 = -2.0 * sig ** 2 * math.log(0.1)
+    yy, xx = np.mgrid[0:H, 0:W]
+    inside = (xx - 17) ** 2 + (yy - 12) ** 2 <= r2
+    np.testing.assert_array_equal(out[1] != 0, inside)
+    dens = lambda y, x: math.exp(-(x * x + y * y) / (2 * sig * sig)) / (2 * math.pi * sig * sig)
+    for (x, y) in [(17, 12), (19, 11), (14, 15), (20, 14)]:
+        mass, _ = integrate.dblquad(dens, x - 17 - 0.5, x - 17 + 0.5, y - 12 - 0.5, y - 12 + 0.5,
+                                    epsabs=1e-13)
+        for c in range(3):
+            assert out[c, y, x] == pytest.approx(v[c] * sig * mass, rel=1e-9)
+    # the disc holds 1 - 0.1 of the continuous Gaussian's mass (pixelized)
+    assert out[1].sum() == pytest.approx(-0.9 * sig, rel=0.03)
+
+
+def test_spline_transposes_with_the_frame():
+    W, H = 48, 36
+    rng = _rng(160)
+    pts = np.array([[3, 4], [20, 30], [41, 8]])
+    d = rng.standard_normal((1, 4, 32)).astype(np.float32) * 0.3
+    d[0, 3, 0] = 48.0  # sigma about 1.5
+    a = O.splines(O.params(W, H), [0, 3], pts, d, np.zeros((3, H, W)))
+    b = O.splines(O.params(H, W), [0, 3], pts[:, ::-1], d, np.zeros((3, W, H)))
+    np.testing.assert_allclose(a, b.transpose(0, 2, 1), atol=1e-14)
+    assert np.abs(a).max() > 0.01
+
+
+def test_spline_values_follow_the_arc_length():
+    # a horizontal line at integer points and a narrow sigma: pixel (x0 + j,
+    # y0) sees point j alone, carrying ContinuousIDCT(31 j / L)
+    W, H = 80, 16
+    x0, y0, x1 = 6, 7, 66
+    sig = 0.3
+    d = np.zeros((1, 4, 32), np.float32)
+    d[0, 0, 1] = 5.0
+    d[0, 0, 3] = -2.0
+    d[0, 3, 0] = 32.0 * sig
+    out = O.splines(O.params(W, H), [0, 2], [[x0, y0], [x1, y0]], d, np.zeros((3, H, W)))
+    L = x1 - x0
+    sig = O.spline_idct(d[0, 3], 0.0)  # 0.3 rounded to binary32 via its coefficient
+    g = math.erf(0.5 / (math.sqrt(2) * sig)) * 2
+    for j in range(L + 1):
+        want = O.spline_idct(d[0, 0], 31.0 * j / L) * sig / 4.0 * g * g
+        assert out[0, y0, x0 + j] == pytest.approx(want, rel=1e-12, abs=1e-15)
+    assert np.count_nonzero(out[0]) == L + 1
+    # the first coefficient alone would give the same value at every pixel
+    assert abs(out[0, y0, x0] - out[0, y0, x1]) > 0.01
+
+
+def test_splines_follow_dots_and_precede_noise():
+    W, H = 40, 24
+    f = _frame_of(0, W, H, _rng(170).integers(-200, 200, size=(3, 3, 5)),
+                  ac=_rng(171).integers(-4, 5, size=(3, 24, 40)).astype(np.int32))
+    f["dots"] = np.array([_dot(60, 40, 9, 4, 5, 1, (2, 7, 3), 0)])
+    f["spline_offsets"] = np.array([0, 3, 4], np.int32)
+    f["spline_points"] = np.array([[2, 3], [20, 15], [35, 4], [10, 18]], np.int32)
+    f["spline_dct"] = np.stack([_spline_dct((0.1, 0.3, -0.2), 1.2), _spline_dct((0.0, 0.5, 0.1), 2.0)])
+    p = O.params(W, H, dc_mul=(0.004, 0.004, 0.004), epf_iters=1, noise=1,
+                 noise_lut=np.full(16, 0.1), dot_colour_quant=(0.01, 0.02, 0.03))
+    st = O.decode_stages(p, f)
+    np.testing.assert_array_equal(
+        st["splines"], O.splines(p, f["spline_offsets"], f["spline_points"], f["spline_dct"],
+                                 st["dots"]))
+    np.testing.assert_array_equal(st["noise"], O.noise(p, st["splines"]))
+    np.testing.assert_allclose(O.decode(p, f), st["rgb"], atol=1e-12)
+    bad = dict(f, spline_points=np.array([[2, 3], [2, 3], [35, 4], [10, 18]], np.int32))
+    with pytest.raises(O.OracleError):
+        O.decode(p, bad)
+
+
+# --------------------------------------------------------------------------
 # Noise (K.5)
 # --------------------------------------------------------------------------
 
