@@ -149,6 +149,13 @@ typedef struct {
    * does not give (finite).  The batch functions reject dots. */
   int32_t  num_dots;
   float    dot_colour_quant[3];
+  /* Splines of K.4: the number of splines in io (0: none), rendered after
+   * the dots (and before the noise); like dots they make Gaborish a pass of
+   * its own.  num_spline_points: the control points of all of them (at
+   * least one each, at most 2^22 in all); it sizes the curve scratch.  The
+   * batch functions reject splines. */
+  int32_t  num_splines;
+  int32_t  num_spline_points;
 } jxlr_frame_params;
 
 /* Input and output planes of one frame.  With Wb = ceil(xsize/8),
@@ -204,6 +211,18 @@ typedef struct {
    * each: x, y (times 5), sigma_x, sigma_y, angle, sign_intensity,
    * intensity[3], is_circle. */
   const int32_t* dots;
+  /* K.4 splines (C.4.7, already decoded, dequantized and recorrelated):
+   * spline_offsets int32 [p->num_splines + 1], rising, from 0 to at most
+   * p->num_spline_points: spline s has the control points
+   * [spline_offsets[s], spline_offsets[s + 1]) of spline_points, int32 (x, y)
+   * pairs [p->num_spline_points][2]; spline_dct float [p->num_splines][4][32]:
+   * the DCT32 coefficients of X, Y, B and sigma along the arc length.  A
+   * spline with no control point, offsets out of range, two consecutive equal
+   * control points or an arc length above 2^24 is skipped, with the sticky
+   * device flag set (bit 2). */
+  const int32_t* spline_offsets;
+  const int32_t* spline_points;
+  const float* spline_dct;
 } jxlr_frame_io;
 
 typedef struct jxlr_ctx jxlr_ctx;
@@ -296,7 +315,7 @@ jxlr_status jxlr_patches(jxlr_ctx* ctx, const jxlr_frame_params* p, const jxlr_f
                          float* xyb, size_t xyb_stride, hipStream_t stream);
 
 /* J.4 alone, xyb_in -> xyb_out (distinct buffers): the Gaborish pass that
- * precedes the dots. */
+ * precedes the dots and the splines. */
 jxlr_status jxlr_gaborish(jxlr_ctx* ctx, const jxlr_frame_params* p, const float* xyb_in,
                           float* xyb_out, size_t xyb_stride, hipStream_t stream);
 
@@ -307,13 +326,29 @@ jxlr_status jxlr_gaborish(jxlr_ctx* ctx, const jxlr_frame_params* p, const float
 jxlr_status jxlr_dots(jxlr_ctx* ctx, const jxlr_frame_params* p, const jxlr_frame_io* io,
                       float* xyb, size_t xyb_stride, hipStream_t stream);
 
+/* K.4: renders the splines of io into the XYB planes in place.  Each spline
+ * becomes the sequence of points sampling its centripetal Catmull-Rom curve
+ * (16 per control point interval, mirrored points extending both ends), the
+ * points at unit arc length along the polyline through them (and its last
+ * point), and at each such point the ContinuousIDCT of its four coefficient
+ * sets at 31 l / L; every pixel whose squared distance from the point is at
+ * most -2 sigma^2 log(0.1) gets value d sigma / 4 times the two erf
+ * differences over the pixel's extent (a point with sigma <= 0 adds
+ * nothing).  Float atomics: overlapping footprints sum in any order.
+ * scratch: device memory of at least jxlr_spline_scratch_bytes(p) bytes,
+ * owned by the caller, overwritten. */
+size_t jxlr_spline_scratch_bytes(const jxlr_frame_params* p);
+jxlr_status jxlr_splines(jxlr_ctx* ctx, const jxlr_frame_params* p, const jxlr_frame_io* io,
+                         float* xyb, size_t xyb_stride, void* scratch, size_t scratch_bytes,
+                         hipStream_t stream);
+
 /* K.5.2: the three pseudorandom channels of every 256x256 group of the frame
  * (frame-sized planes, float [3][ysize][xsize], row stride xsize, device
  * memory owned by the caller); they depend on the frame size only. */
 jxlr_status jxlr_noise_channels(jxlr_ctx* ctx, const jxlr_frame_params* p, float* raw,
                                 hipStream_t stream);
 
-/* Gaborish (J.4, when p->gab and there are no dots), noise (K.5, when
+/* Gaborish (J.4, when p->gab and there are neither dots nor splines), noise (K.5, when
  * p->noise, from io->noise_raw) and XYB -> RGB (L.2) into io->out in
  * p->out_format. */
 jxlr_status jxlr_finish(jxlr_ctx* ctx, const jxlr_frame_params* p, const jxlr_frame_io* io,

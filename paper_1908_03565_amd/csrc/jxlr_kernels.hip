@@ -2143,6 +2143,253 @@ __global__ __launch_bounds__(256) void dots_kernel(DotArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// Splines (K.4), after the dots.  One workgroup per spline: its threads
+// sample the centripetal Catmull-Rom curve (each point of the sequence C is a
+// closed form of its window of four extended control points), scan the
+// lengths of the polyline's pieces into arc positions, then take the points
+// P at unit arc length, one per thread: each evaluates the four
+// ContinuousIDCTs (X, Y, B, sigma) and adds its erf footprint with float
+// atomics.  Positions, arc lengths, values and the footprint test are
+// binary64 (the test decides whole pixels at a tenth of the peak); only the
+// sums into the frame are binary32.  The points go in chunks of the group's
+// size: a thread per point computes its position and values, then a wave per
+// point adds its footprint, a lane per pixel.
+
+constexpr int kSplineThreads = 256;
+// longest arc length rendered; a longer spline is rejected (device flag)
+constexpr double kSplineMaxArc = 16777216.0;
+
+struct SplineArgs {
+  int W, H;
+  float* xyb;
+  size_t stride;
+  const int32_t* offsets;  // num + 1 control point offsets
+  const int32_t* points;   // total (x, y) pairs
+  const float* dct;        // [num][4][32]
+  int num, total;
+  double* scratch;         // x, y and arc position of C: 3 planes of 16 * total
+  int* status;
+  const DeviceTables* T;
+};
+
+// Extended control point e (0 .. n + 1) of a spline with n >= 2 control
+// points q: the ends are the mirrored first and last points.
+__device__ inline void spline_ext(const int32_t* q, int n, int e, double& x, double& y) {
+  if (e == 0) {
+    x = 2.0 * q[0] - q[2];
+    y = 2.0 * q[1] - q[3];
+  } else if (e == n + 1) {
+    x = 2.0 * q[2 * n - 2] - q[2 * n - 4];
+    y = 2.0 * q[2 * n - 1] - q[2 * n - 3];
+  } else {
+    x = q[2 * e - 2];
+    y = q[2 * e - 1];
+  }
+}
+
+__global__ __launch_bounds__(kSplineThreads) void spline_kernel(SplineArgs a) {
+  __shared__ double s_scan[kSplineThreads];
+  __shared__ double s_dct[4][32];
+  __shared__ double s_pt[7][kSplineThreads];  // x, y, d sigma / 4, sigma, X, Y, B
+  __shared__ int s_bad;
+  const int sp = blockIdx.x, tid = threadIdx.x;
+  const int o0 = a.offsets[sp], o1 = a.offsets[sp + 1];
+  if (o0 < 0 || o1 > a.total || o1 <= o0) {  // uniform over the group
+    if (tid == 0) atomicOr(a.status, 4);
+    return;
+  }
+  const int n = o1 - o0;
+  const int32_t* q = a.points + 2 * size_t(o0);
+  if (tid == 0) s_bad = 0;
+  __syncthreads();
+  for (int i = tid; i + 1 < n; i += kSplineThreads)
+    if (q[2 * i] == q[2 * i + 2] && q[2 * i + 1] == q[2 * i + 3]) s_bad = 1;
+  for (int i = tid; i < 128; i += kSplineThreads)
+    s_dct[i >> 5][i & 31] = a.dct[size_t(sp) * 128 + i];
+  __syncthreads();
+  if (s_bad) {  // two consecutive control points coincide
+    if (tid == 0) atomicOr(a.status, 4);
+    return;
+  }
+
+  // the sequence C: per window w of the extended points, its second point
+  // then 15 samples at steps of one 16th of the window's middle knot interval
+  const int m = n == 1 ? 1 : 16 * (n - 1) + 1;
+  double* cx = a.scratch + 16 * size_t(o0);
+  double* cy = cx + 16 * size_t(a.total);
+  double* arc = cy + 16 * size_t(a.total);
+  for (int i = tid; i < m; i += kSplineThreads) {
+    const int w = i >> 4, step = i & 15;
+    double x, y;
+    if (i == m - 1) {
+      x = q[2 * n - 2];
+      y = q[2 * n - 1];
+    } else if (step == 0) {
+      x = q[2 * w];
+      y = q[2 * w + 1];
+    } else {
+      double px[4], py[4], tk[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) spline_ext(q, n, w + k, px[k], py[k]);
+      tk[0] = 0.0;
+#pragma unroll
+      for (int k = 1; k < 4; ++k) {
+        const double dx = px[k] - px[k - 1], dy = py[k] - py[k - 1];
+        tk[k] = tk[k - 1] + pow(dx * dx + dy * dy, 0.25);
+      }
+      const double t = tk[1] + step * (tk[2] - tk[1]) / 16.0;
+      double ax[3], ay[3];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const double f = (t - tk[k]) / (tk[k + 1] - tk[k]);
+        ax[k] = px[k] + f * (px[k + 1] - px[k]);
+        ay[k] = py[k] + f * (py[k + 1] - py[k]);
+      }
+      double bx[2], by[2];
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+        const double f = (t - tk[k]) / (tk[k + 2] - tk[k]);
+        bx[k] = ax[k] + f * (ax[k + 1] - ax[k]);
+        by[k] = ay[k] + f * (ay[k + 1] - ay[k]);
+      }
+      const double f = (t - tk[1]) / (tk[2] - tk[1]);
+      x = bx[0] + f * (bx[1] - bx[0]);
+      y = by[0] + f * (by[1] - by[0]);
+    }
+    cx[i] = x;
+    cy[i] = y;
+  }
+  __syncthreads();
+
+  // arc positions: an inclusive scan of the piece lengths, chunk by chunk
+  if (tid == 0) arc[0] = 0.0;
+  double carry = 0.0;
+  for (int base = 0; base < m - 1; base += kSplineThreads) {
+    const int i = base + tid;
+    s_scan[tid] = i < m - 1 ? hypot(cx[i + 1] - cx[i], cy[i + 1] - cy[i]) : 0.0;
+    __syncthreads();
+    for (int off = 1; off < kSplineThreads; off <<= 1) {
+      const double v = tid >= off ? s_scan[tid - off] : 0.0;
+      __syncthreads();
+      s_scan[tid] += v;
+      __syncthreads();
+    }
+    if (i < m - 1) arc[i + 1] = carry + s_scan[tid];
+    carry += s_scan[kSplineThreads - 1];
+    __syncthreads();
+  }
+  const double L = carry;
+  if (L > kSplineMaxArc) {
+    if (tid == 0) atomicOr(a.status, 4);
+    return;
+  }
+  const double fl = floor(L);
+  const int n_int = int(fl) + 1;
+  const int np = n_int + (m > 1 && fl < L ? 1 : 0);
+
+  const double kPi = 3.14159265358979323846;
+  const double kLog01 = -2.302585092994045684;  // log(0.1)
+  const size_t plane = size_t(a.H) * a.stride;
+  const int lane = tid & 63, wave = tid >> 6;
+  for (int base = 0; base < np; base += kSplineThreads) {
+    // one thread per point: position, values and amplitude into LDS
+    const int j = base + tid;
+    if (j < np) {
+      double px, py, l, d = 1.0;
+      if (j >= n_int) {  // the last point of C, where the walk stopped short
+        px = cx[m - 1];
+        py = cy[m - 1];
+        l = L;
+        d = L - fl;
+      } else if (j == 0) {
+        px = cx[0];
+        py = cy[0];
+        l = 0.0;
+      } else {
+        l = double(j);
+        // the first piece i whose end lies at or beyond l
+        int lo = 0, hi = m - 2;
+        while (lo < hi) {
+          const int mid = (lo + hi) >> 1;
+          if (arc[mid + 1] >= l) hi = mid;
+          else lo = mid + 1;
+        }
+        const double len = arc[lo + 1] - arc[lo];
+        const double f = len > 0.0 ? (l - arc[lo]) / len : 0.0;
+        px = cx[lo] + f * (cx[lo + 1] - cx[lo]);
+        py = cy[lo] + f * (cy[lo + 1] - cy[lo]);
+      }
+      const double t = L > 0.0 ? 31.0 * l / L : 0.0;
+      double v[4] = {0.0, 0.0, 0.0, 0.0};
+      for (int k = 0; k < 32; ++k) {
+        const double ck = a.T->spline_scale[k] * cos(k * (kPi / 32.0) * (t + 0.5));
+#pragma unroll
+        for (int c = 0; c < 4; ++c) v[c] += ck * s_dct[c][k];
+      }
+      s_pt[0][tid] = px;
+      s_pt[1][tid] = py;
+      s_pt[2][tid] = d * v[3] / 4.0;
+      s_pt[3][tid] = v[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) s_pt[4 + c][tid] = v[c];
+    }
+    __syncthreads();
+    // one wave per point: its lanes take the pixels of the footprint's
+    // bounding box, so each atomic instruction adds to distinct pixels
+    const int cnt = min(kSplineThreads, np - base);
+    for (int i = wave; i < cnt; i += kSplineThreads / 64) {
+      const double px = s_pt[0][i], py = s_pt[1][i], amp = s_pt[2][i], sigma = s_pt[3][i];
+      if (!(sigma > 0.0)) continue;  // no footprint
+      const double r2 = -2.0 * sigma * sigma * kLog01;
+      const double r = sqrt(r2);
+      const double s2s = 1.4142135623730951 * sigma;
+      const double xlo = fmax(0.0, floor(px - r)), xhi = fmin(a.W - 1.0, ceil(px + r));
+      const double ylo = fmax(0.0, floor(py - r)), yhi = fmin(a.H - 1.0, ceil(py + r));
+      if (xlo > xhi || ylo > yhi) continue;
+      const int x0 = int(xlo), y0 = int(ylo);
+      const int bw = int(xhi - xlo) + 1, bh = int(yhi - ylo) + 1;
+      const double v0 = s_pt[4][i], v1 = s_pt[5][i], v2 = s_pt[6][i];
+      if (bw < 32 && bh < 32) {
+        // erf at the pixel edges, x edges in lanes 0..bw and y edges in lanes
+        // 32..32+bh; lane k then holds the difference over column (row) k
+        const double arg = lane < 32 ? (px - (x0 + lane) + 0.5) / s2s
+                                     : (py - (y0 + lane - 32) + 0.5) / s2s;
+        const double e = erf(arg);
+        const double diff = e - __shfl_down(e, 1);
+        for (int k0 = 0; k0 < bw * bh; k0 += 64) {  // uniform over the wave
+          const int k = k0 + lane;
+          const bool in = k < bw * bh;
+          const int row = in ? k / bw : 0, col = in ? k - row * bw : 0;
+          const double ex = __shfl(diff, col), ey = __shfl(diff, 32 + row);
+          const double dx = px - (x0 + col), dy = py - (y0 + row);
+          if (in && dx * dx + dy * dy <= r2) {
+            const double g = amp * ex * ey;
+            const size_t o = size_t(y0 + row) * a.stride + (x0 + col);
+            atomicAdd(a.xyb + o, float(v0 * g));
+            atomicAdd(a.xyb + plane + o, float(v1 * g));
+            atomicAdd(a.xyb + 2 * plane + o, float(v2 * g));
+          }
+        }
+      } else {
+        // a wide footprint: both differences per pixel
+        for (int k = lane; k < bw * bh; k += 64) {
+          const int row = k / bw, col = k - row * bw;
+          const double dx = px - (x0 + col), dy = py - (y0 + row);
+          if (dx * dx + dy * dy > r2) continue;
+          const double g = amp * (erf((dx + 0.5) / s2s) - erf((dx - 0.5) / s2s)) *
+                           (erf((dy + 0.5) / s2s) - erf((dy - 0.5) / s2s));
+          const size_t o = size_t(y0 + row) * a.stride + (x0 + col);
+          atomicAdd(a.xyb + o, float(v0 * g));
+          atomicAdd(a.xyb + plane + o, float(v1 * g));
+          atomicAdd(a.xyb + 2 * plane + o, float(v2 * g));
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Noise channels (K.5.2).  One workgroup per 256x256 group and channel; each
 // thread runs one of the eight generators over 16 rows: it seeds the
 // generator (SplitMix64 chain), jumps it ahead to its first step with the
@@ -2428,6 +2675,9 @@ jxlr_status check_params(const jxlr_frame_params* p) {
     return JXLR_E_PARAM;
   if (p->noise < 0 || p->noise > 1) return JXLR_E_PARAM;
   if (p->num_patches < 0 || p->num_dots < 0) return JXLR_E_PARAM;
+  if (p->num_splines < 0 || p->num_spline_points < 0 || p->num_spline_points > (1 << 22) ||
+      (p->num_splines > 0 && p->num_spline_points < p->num_splines))
+    return JXLR_E_PARAM;
   for (int c = 0; c < 3; ++c)
     if (!std::isfinite(p->dot_colour_quant[c])) return JXLR_E_PARAM;
   for (int i = 0; i < 16; ++i)
@@ -2588,6 +2838,15 @@ int xyb_buffers(const jxlr_frame_params* p) {
   if (p->epf_iters == 0) return 1;
   return p->qco && p->epf_iters > 1 ? 3 : 2;
 }
+// K.4 curve samples: x, y and arc position of up to 16 per control point.
+size_t spline_bytes(const jxlr_frame_params* p) {
+  return p->num_splines > 0 ? round256(size_t(3) * 16 * sizeof(double) * p->num_spline_points)
+                            : 0;
+}
+// With dots or splines, Gaborish runs as its own pass before them.
+bool gab_pass(const jxlr_frame_params* p) {
+  return p->gab && (p->num_dots > 0 || p->num_splines > 0);
+}
 // Annex H sums, when AC prediction is on.
 size_t pred_bytes(const jxlr_frame_params* p) {
   return p->ac_prediction ? round256(size_t(12) * sizeof(float) * blocks_of(p->xsize) *
@@ -2601,7 +2860,12 @@ extern "C" {
 size_t jxlr_workspace_bytes(const jxlr_frame_params* p) {
   if (check_params(p) != JXLR_OK) return 0;
   return info_bytes(p) + xyb_buffers(p) * xyb_bytes(p) + pred_bytes(p) +
-         (p->noise ? xyb_bytes(p) : 0) + (p->num_dots > 0 && p->gab ? xyb_bytes(p) : 0);
+         (p->noise ? xyb_bytes(p) : 0) + (gab_pass(p) ? xyb_bytes(p) : 0) + spline_bytes(p);
+}
+
+size_t jxlr_spline_scratch_bytes(const jxlr_frame_params* p) {
+  if (check_params(p) != JXLR_OK) return 0;
+  return spline_bytes(p);
 }
 
 }  // extern "C"
@@ -2741,7 +3005,7 @@ jxlr_status make_finish_args(jxlr_ctx* ctx, const jxlr_frame_params* p, const jx
   a.in = xyb;
   a.stride = stride;
   // with dots, Gaborish runs as its own pass before them
-  a.gab = p->gab && p->num_dots == 0;
+  a.gab = p->gab && !gab_pass(p);
   for (int c = 0; c < 3; ++c) {
     // J.4: weights 1, w1, w2 rescaled to sum to 1
     const double w1 = p->gab_w1[c], w2 = p->gab_w2[c];
@@ -2913,6 +3177,26 @@ jxlr_status jxlr_dots(jxlr_ctx* ctx, const jxlr_frame_params* p, const jxlr_fram
   return launch_status(hipGetLastError());
 }
 
+jxlr_status jxlr_splines(jxlr_ctx* ctx, const jxlr_frame_params* p, const jxlr_frame_io* io,
+                         float* xyb, size_t stride, void* scratch, size_t scratch_bytes,
+                         hipStream_t stream) {
+  if (!ctx || !io || !xyb) return JXLR_E_NULL;
+  jxlr_status st = check_params(p);
+  if (st) return st;
+  if (stride < p->xsize) return JXLR_E_SIZE;
+  if (p->num_splines == 0) return JXLR_OK;
+  if (!io->spline_offsets || !io->spline_points || !io->spline_dct || !scratch)
+    return JXLR_E_NULL;
+  if (scratch_bytes < spline_bytes(p)) return JXLR_E_WORKSPACE;
+  SplineArgs a{int(p->xsize), int(p->ysize), xyb, stride, io->spline_offsets, io->spline_points,
+               io->spline_dct, p->num_splines, p->num_spline_points,
+               static_cast<double*>(scratch), ctx->status, ctx->tables};
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return JXLR_E_HIP;
+  hipLaunchKernelGGL(spline_kernel, dim3(p->num_splines), dim3(kSplineThreads), 0, stream, a);
+  return launch_status(hipGetLastError());
+}
+
 jxlr_status jxlr_noise_channels(jxlr_ctx* ctx, const jxlr_frame_params* p, float* raw,
                                 hipStream_t stream) {
   if (!ctx || !raw) return JXLR_E_NULL;
@@ -3022,14 +3306,19 @@ jxlr_status jxlr_decode(jxlr_ctx* ctx, const jxlr_frame_params* p, const jxlr_fr
     if ((st = jxlr_noise_channels(ctx, p, raw, stream))) return st;
     iop.noise_raw = raw;
   }
-  if (p->num_dots > 0) {
-    // K.1: Gaborish, then the dots; the finish then skips its Gaborish
-    if (p->gab) {
+  if (p->num_dots > 0 || p->num_splines > 0) {
+    // K.1: Gaborish, then the dots and the splines; the finish then skips
+    // its Gaborish
+    if (gab_pass(p)) {
       float* gab = reinterpret_cast<float*>(tail);
+      tail += xyb_bytes(p);
       if ((st = jxlr_gaborish(ctx, p, cur, gab, stride, stream))) return st;
       cur = gab;
     }
-    if ((st = jxlr_dots(ctx, p, io, cur, stride, stream))) return st;
+    if (p->num_dots > 0 && (st = jxlr_dots(ctx, p, io, cur, stride, stream))) return st;
+    if (p->num_splines > 0 &&
+        (st = jxlr_splines(ctx, p, io, cur, stride, tail, spline_bytes(p), stream)))
+      return st;
   }
   return jxlr_finish(ctx, p, &iop, cur, stride, stream);
 }
@@ -3126,7 +3415,7 @@ size_t jxlr_batch_workspace_bytes(int n, const jxlr_frame_params* p) {
   if (n <= 0 || !p) return 0;
   for (int i = 0; i < n; ++i)
     if (check_params(&p[i]) != JXLR_OK || p[i].qco || p[i].ac_prediction || p[i].noise ||
-        p[i].num_patches || p[i].num_dots)
+        p[i].num_patches || p[i].num_dots || p[i].num_splines)
       return 0;
   return batch_layout(n, p).total;
 }
@@ -3140,7 +3429,8 @@ jxlr_status jxlr_batch_prepare(jxlr_ctx* ctx, int n, const jxlr_frame_params* p,
     jxlr_status st = check_params(&p[i]);
     if (st) return st;
     // the batch stages have no constraint, prediction, patch, dot or noise stage
-    if (p[i].qco || p[i].ac_prediction || p[i].noise || p[i].num_patches || p[i].num_dots)
+    if (p[i].qco || p[i].ac_prediction || p[i].noise || p[i].num_patches || p[i].num_dots ||
+        p[i].num_splines)
       return JXLR_E_PARAM;
   }
   const BatchLayout L = batch_layout(n, p);

@@ -578,6 +578,8 @@ bool build_tables(DeviceTables* t) {
   }
   t->pred_sf = float(scale_f(2, 8, 1));
   t->pred_s8_1 = float(transform_scale(8, 1));
+  for (int k = 0; k < 32; ++k)
+    t->spline_scale[k] = scale_d(32, k) * (k == 0 ? 1.0 / (4.0 * std::sqrt(2.0)) : 0.25);
   build_mfma_operands(t);
   for (int j = 0; j < 16; ++j)
     for (int i = 0; i < 16; ++i) t->afv[j][i] = float(kAfvBasis[j][i]);

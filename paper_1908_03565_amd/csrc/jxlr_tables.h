@@ -104,6 +104,9 @@ struct DeviceTables {
   // power (bit r of the advanced state is the parity of the row ANDed with
   // the state), as two words.
   uint64_t noise_jump[14][128][2];
+  // Splines (K.4): DCTScale(k) of ContinuousIDCT, D(32, k) of I.2.6.1 times
+  // 1 / (4 sqrt 2) at k = 0 and 1/4 elsewhere, in binary64.
+  double spline_scale[32];
 };
 
 // Fills t on the host.  Returns false if a dequantization matrix entry is not

@@ -49,6 +49,8 @@ class FrameParams(C.Structure):
         ("num_patches", C.c_int32),
         ("num_dots", C.c_int32),
         ("dot_colour_quant", C.c_float * 3),
+        ("num_splines", C.c_int32),
+        ("num_spline_points", C.c_int32),
     ]
 
 
@@ -65,6 +67,9 @@ class FrameIO(C.Structure):
         ("patch_place", C.c_void_p), ("patch_samples", C.c_void_p),
         ("patch_samples_count", C.c_size_t),
         ("dots", C.c_void_p),
+        ("spline_offsets", C.c_void_p),
+        ("spline_points", C.c_void_p),
+        ("spline_dct", C.c_void_p),
     ]
 
 
@@ -126,6 +131,9 @@ _SIGS = {
                        C.c_void_p], C.c_int),
     "jxlr_dots": ([C.c_void_p, C.POINTER(FrameParams), C.POINTER(FrameIO), C.c_void_p, C.c_size_t,
                    C.c_void_p], C.c_int),
+    "jxlr_spline_scratch_bytes": ([C.POINTER(FrameParams)], C.c_size_t),
+    "jxlr_splines": ([C.c_void_p, C.POINTER(FrameParams), C.POINTER(FrameIO), C.c_void_p,
+                      C.c_size_t, C.c_void_p, C.c_size_t, C.c_void_p], C.c_int),
     "jxlr_noise_channels": ([C.c_void_p, C.POINTER(FrameParams), C.c_void_p, C.c_void_p], C.c_int),
     "jxlr_qco_pass": ([C.c_void_p, C.POINTER(FrameParams), C.POINTER(FrameIO), C.c_void_p,
                        C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p], C.c_int),
@@ -249,6 +257,12 @@ class DeviceFrame:
                               if self.patch_place is not None else None)
         dt = frame.get("dots")
         self.dots = t(dt, np.int32) if dt is not None and len(dt) else None
+        # K.4 splines, if the frame has any
+        so = frame.get("spline_offsets")
+        has = so is not None and len(so) > 1
+        self.spline_offsets = t(so, np.int32) if has else None
+        self.spline_points = t(frame["spline_points"], np.int32) if has else None
+        self.spline_dct = t(frame["spline_dct"], np.float32) if has else None
 
     def clone(self):
         """A copy in distinct device memory."""
@@ -259,6 +273,9 @@ class DeviceFrame:
         c.patch_place = None if self.patch_place is None else self.patch_place.clone()
         c.patch_samples = None if self.patch_samples is None else self.patch_samples.clone()
         c.dots = None if self.dots is None else self.dots.clone()
+        for k in ("spline_offsets", "spline_points", "spline_dct"):
+            v = getattr(self, k, None)
+            setattr(c, k, None if v is None else v.clone())
         return c
 
     def io(self, out=None, ac_pred=None, noise_raw=None):
@@ -271,6 +288,10 @@ class DeviceFrame:
             io.patch_samples_count = self.patch_samples.numel()
         if getattr(self, "dots", None) is not None:
             io.dots = self.dots.data_ptr()
+        if getattr(self, "spline_offsets", None) is not None:
+            io.spline_offsets = self.spline_offsets.data_ptr()
+            io.spline_points = self.spline_points.data_ptr()
+            io.spline_dct = self.spline_dct.data_ptr()
         for c in range(3):
             io.ac[c] = self.ac[c].data_ptr()
             io.dc[c] = self.dc[c].data_ptr()
@@ -375,6 +396,18 @@ class Context:
     def dots(self, p, df, xyb, stream=None):
         _check(lib().jxlr_dots(self.handle, C.byref(p), C.byref(df.io()), xyb.data_ptr(),
                                xyb.shape[2], _stream_handle(stream)), "dots")
+
+    def spline_scratch(self, p):
+        import torch
+        return torch.empty(max(1, lib().jxlr_spline_scratch_bytes(C.byref(p))), dtype=torch.uint8,
+                           device=f"cuda:{self.device}")
+
+    def splines(self, p, df, xyb, scratch=None, stream=None):
+        if scratch is None:
+            scratch = self.spline_scratch(p)
+        _check(lib().jxlr_splines(self.handle, C.byref(p), C.byref(df.io()), xyb.data_ptr(),
+                                  xyb.shape[2], scratch.data_ptr(), scratch.numel(),
+                                  _stream_handle(stream)), "splines")
 
     def noise_channels(self, p, raw, stream=None):
         _check(lib().jxlr_noise_channels(self.handle, C.byref(p), raw.data_ptr(),

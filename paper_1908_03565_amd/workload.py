@@ -230,6 +230,47 @@ def crop(mother, x0, y0, W, H, epf_iters=None, out_format=None, name=None):
                 out_format=mother["out_format"] if out_format is None else out_format)
 
 
+def splines(W, H, n, seed, max_points=12, step=(8, 48), sigma=(0.6, 3.0), value=0.3):
+    """Synthetic already-decoded splines (K.4) for a W x H frame: n splines of
+    1..max_points integer control points, a random walk of steps up to
+    `step` pixels starting anywhere in (or just outside) the frame, no two
+    consecutive points equal; DCT32 coefficients of X, Y, B with a DC of
+    magnitude up to 32 * value and decaying higher terms, and of sigma with
+    a DC of 32 * U(sigma) and small higher terms.  Returns (offsets (n + 1,)
+    int32, points (m, 2) int32, dct (n, 4, 32) float32)."""
+    rng = np.random.default_rng(seed)
+    counts = rng.integers(1, max_points + 1, size=n)
+    offsets = np.concatenate([[0], np.cumsum(counts)]).astype(np.int32)
+    pts = []
+    for c in counts:
+        x, y = int(rng.integers(-16, W + 16)), int(rng.integers(-16, H + 16))
+        pts.append((x, y))
+        for _ in range(c - 1):
+            while True:
+                ang = rng.uniform(0, 2 * np.pi)
+                r = rng.uniform(*step)
+                nx, ny = x + int(round(r * np.cos(ang))), y + int(round(r * np.sin(ang)))
+                if (nx, ny) != (x, y):
+                    break
+            x, y = nx, ny
+            pts.append((x, y))
+    dct = np.zeros((n, 4, 32), np.float32)
+    decay = 1.0 / (1.0 + np.arange(32))
+    dct[:, :3, :] = (rng.standard_normal((n, 3, 32)) * decay * 32 * value / 3).astype(np.float32)
+    dct[:, :3, 0] = rng.uniform(-32 * value, 32 * value, size=(n, 3))
+    dct[:, 3, :] = (rng.standard_normal((n, 32)) * decay * 2.0).astype(np.float32)
+    dct[:, 3, 0] = 32 * rng.uniform(*sigma, size=n)
+    return offsets, np.array(pts, np.int32), dct
+
+
+def with_splines(f, n, seed, **kw):
+    """The frame dict f with n synthetic splines added (see splines())."""
+    off, pts, dct = splines(f["xsize"], f["ysize"], n, seed, **kw)
+    f = dict(f)
+    f["spline_offsets"], f["spline_points"], f["spline_dct"] = off, pts, dct
+    return f
+
+
 def c5_mother():
     return frame(4096, 4096, seed=5, epf_iters=2, gab=1, name="c5_mother_4096x4096")
 

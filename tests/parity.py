@@ -90,15 +90,21 @@ def gpu_stages(ctx, p, df):
             cur = xyb.clone()
         ctx.patches(p, df, cur)
         res["patches"] = cur.cpu().numpy()
-    if p.num_dots:
+    if p.num_dots or p.num_splines:
+        # Gaborish as its own pass before them
         if p.gab:
             g = ctx.empty_xyb(p)
             ctx.gaborish(p, cur, g)
             cur = g
         elif cur is xyb:
             cur = xyb.clone()
+        res["gab"] = cur.cpu().numpy()
+    if p.num_dots:
         ctx.dots(p, df, cur)
         res["dots"] = cur.cpu().numpy()
+    if p.num_splines:
+        ctx.splines(p, df, cur)
+        res["splines"] = cur.cpu().numpy()
     out = ctx.empty_out(p)
     raw = None
     if p.noise:

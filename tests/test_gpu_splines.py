@@ -1,0 +1,155 @@
+"""GPU parity of splines (K.4): synthetic already-decoded splines (one to
+twelve control points, starting in or just outside the frame, single points
+among them) rendered by the HIP kernel after a separate Gaborish pass, against
+the FP64 oracle; a frame whose curves lie far from the origin; then end to end
+with dots before them and the noise after them; ill-formed splines skipped
+with the device flag set."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1908_03565_amd import workload as wl
+from tests import parity as P
+
+pytestmark = pytest.mark.gpu
+
+# binary64 positions, values and footprints; binary32 sums of up to a few
+# dozen overlapping footprints per sample
+SPLINE_TOL = 2e-6
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_1908_03565_amd import jxlr as J
+    return J.Context(0)
+
+
+def _stage(ctx, p, f, base):
+    """The splines kernel alone on `base` (3, H, W) binary32."""
+    import torch
+    from paper_1908_03565_amd import jxlr as J
+    df = J.DeviceFrame(f)
+    xyb = torch.from_numpy(np.ascontiguousarray(base, np.float32)).to("cuda:0")
+    ctx.splines(p, df, xyb)
+    torch.cuda.synchronize()
+    return xyb.cpu().numpy().astype(np.float64)
+
+
+@pytest.mark.parametrize("W,H,n,seed", [(192, 136, 40, 181), (131, 77, 25, 182), (256, 264, 120, 183),
+                                        # centres far from the origin
+                                        (2056, 96, 60, 184)])
+def test_splines_stage_against_oracle(ctx, W, H, n, seed):
+    from paper_1908_03565_amd import jxlr as J
+    f = wl.with_splines(wl.small(W, H, seed=seed, epf_iters=0), n, seed)
+    npts = len(f["spline_points"])
+    p = J.params(W, H, num_splines=n, num_spline_points=npts)
+    base = np.random.default_rng(seed).uniform(-0.5, 0.5, size=(3, H, W)).astype(np.float32)
+    print(f"[splines] {W}x{H} n={n} points={npts}", flush=True)
+    got = _stage(ctx, p, f, base)
+    assert ctx.device_status() == 0
+    want, near = O.splines(O.params(W, H), f["spline_offsets"], f["spline_points"],
+                           f["spline_dct"], base.astype(np.float64), want_near=True)
+    err = np.abs(got - want)[:, ~near].max()
+    moved = np.abs(want - base).max()
+    print("splines err", err, "moved", moved, "near", int(near.sum()))
+    assert err <= SPLINE_TOL * max(1.0, float(np.abs(want).max()))
+    assert moved > 0.05
+    assert near.sum() <= 0.001 * near.size
+
+
+def test_splines_single_points_and_two_point_lines(ctx):
+    from paper_1908_03565_amd import jxlr as J
+    W, H = 96, 80
+    f = dict(wl.small(W, H, seed=185, epf_iters=0))
+    f["spline_offsets"] = np.array([0, 1, 3, 4, 6], np.int32)
+    f["spline_points"] = np.array([[10, 12], [20, 30], [70, 30], [95, 79], [-5, 40], [40, 85]],
+                                  np.int32)
+    d = np.zeros((4, 4, 32), np.float32)
+    d[:, :3, 0] = [[3.2, 6.4, -4.0], [1.0, -2.0, 3.0], [5.0, 5.0, 5.0], [-3.0, 2.0, 1.0]]
+    d[:, 0, 1] = [0.0, 2.0, 0.0, -1.5]
+    d[:, 3, 0] = [64.0, 32.0, 96.0, 40.0]
+    d[1, 3, 2] = 8.0
+    f["spline_dct"] = d
+    p = J.params(W, H, num_splines=4, num_spline_points=6)
+    base = np.zeros((3, H, W), np.float32)
+    got = _stage(ctx, p, f, base)
+    want = O.splines(O.params(W, H), f["spline_offsets"], f["spline_points"], d, base)
+    err = np.abs(got - want).max()
+    print("err", err)
+    assert err <= SPLINE_TOL * max(1.0, float(np.abs(want).max()))
+    assert np.abs(want).max() > 0.05
+
+
+@pytest.mark.parametrize("W,H,seed,n,gab,dots,noise", [(192, 136, 186, 30, 1, 0, 0),
+                                                       (131, 77, 187, 20, 0, 0, 0),
+                                                       (300, 264, 188, 60, 1, 1, 1)])
+def test_splines_end_to_end(ctx, W, H, seed, n, gab, dots, noise):
+    from paper_1908_03565_amd import jxlr as J
+    f = wl.with_splines(wl.small(W, H, seed=seed, epf_iters=1), n, seed)
+    if dots:
+        rng = np.random.default_rng(seed)
+        k = 80
+        dt = np.stack([rng.integers(0, 5 * W, size=k), rng.integers(0, 5 * H, size=k),
+                       rng.integers(0, 16, size=k), rng.integers(0, 16, size=k),
+                       rng.integers(0, 8, size=k), rng.integers(0, 8, size=k),
+                       rng.integers(0, 10, size=k), rng.integers(0, 36, size=k),
+                       rng.integers(0, 10, size=k), np.zeros(k, np.int64)], axis=1)
+        f["dots"] = dt.astype(np.int32)
+    kw = dict(f["params"], gab=gab, noise=noise, noise_lut=np.full(16, 0.05),
+              dot_colour_quant=(0.004, 0.02, 0.01))
+    p = J.params(W, H, num_splines=n, num_spline_points=len(f["spline_points"]),
+                 num_dots=len(f["dots"]) if dots else 0, **kw)
+    df = J.DeviceFrame(f)
+    gpu = P.gpu_stages(ctx, p, df)
+    orc = O.decode_stages(O.params(W, H, **kw), f)
+    mask, _ = P.affected_mask(p, [(g, s) for _, g, s in gpu["epf"]],
+                              [(g, s) for _, g, s in orc["epf"]])
+    if gab:
+        mask = P.dilate(mask, range(-1, 2), range(-1, 2))
+    err = np.abs(gpu["splines"] - orc["splines"])[:, ~mask].max()
+    moved = np.abs(orc["splines"] - (orc["dots"] if dots else orc["gab"])).max()
+    print("splines xyb err", err, "moved", moved)
+    assert err <= SPLINE_TOL * max(1.0, float(np.abs(orc["splines"]).max()))
+    assert moved > 0.05
+    cmp = P.compare_rgb(p, gpu, orc)
+    print({k: v for k, v in cmp.items() if k != "mask"})
+    assert cmp["max_err"] <= P.RGB_TOL
+    out = ctx.empty_out(p)
+    ctx.decode(p, df, out, ctx.workspace(p))
+    assert ctx.device_status() == 0
+    # (float atomics: overlapping contributions may sum in another order)
+    np.testing.assert_allclose(out.cpu().numpy(), gpu["out"], rtol=2e-6, atol=1e-5)
+
+
+def test_ill_formed_splines_are_skipped_with_the_flag(ctx):
+    from paper_1908_03565_amd import jxlr as J
+    W, H = 128, 96
+    f = wl.with_splines(wl.small(W, H, seed=189, epf_iters=0), 6, 189)
+    good = dict(f)
+    # spline 2 gets two equal consecutive control points
+    o = f["spline_offsets"]
+    pts = f["spline_points"].copy()
+    if o[3] - o[2] < 2:
+        pytest.skip("spline 2 of this seed has one control point")
+    pts[o[2] + 1] = pts[o[2]]
+    f = dict(f, spline_points=pts)
+    p = J.params(W, H, num_splines=6, num_spline_points=len(pts))
+    base = np.zeros((3, H, W), np.float32)
+    got = _stage(ctx, p, f, base)
+    assert ctx.device_status() != 0
+    assert ctx.device_status() == 0  # cleared by the read
+    keep = [s for s in range(6) if s != 2]
+    off = [0]
+    kp = []
+    for s in keep:
+        kp.extend(good["spline_points"][o[s]:o[s + 1]])
+        off.append(len(kp))
+    want = O.splines(O.params(W, H), off, kp, good["spline_dct"][keep], base)
+    assert np.abs(got - want).max() <= SPLINE_TOL * max(1.0, float(np.abs(want).max()))
+    # the last spline's end offset beyond the points: that spline alone is skipped
+    f2 = dict(good, spline_offsets=np.array(list(o[:-1]) + [len(pts) + 5], np.int32))
+    got2 = _stage(ctx, p, f2, base)
+    assert ctx.device_status() != 0
+    want2 = O.splines(O.params(W, H), o[:-1], good["spline_points"][:o[-2]],
+                      good["spline_dct"][:5], base)
+    assert np.abs(got2 - want2).max() <= SPLINE_TOL * max(1.0, float(np.abs(want2).max()))

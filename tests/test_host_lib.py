@@ -42,7 +42,8 @@ def test_defaults_agree_with_oracle():
     for name, _ in J.FrameParams._fields_:
         # output format and transform arithmetic are the library's own; the
         # patch and dot counts travel with their arrays on the oracle's side
-        if name in ("out_format", "idct_split", "num_patches", "num_dots"):
+        if name in ("out_format", "idct_split", "num_patches", "num_dots", "num_splines",
+                    "num_spline_points"):
             continue
         a, b = getattr(p, name), getattr(q, name)
         if isinstance(a, C.Array):
@@ -115,7 +116,9 @@ def test_parameter_ranges():
         assert J.validate_maps_host(p, f) == 7
         assert J.workspace_bytes(p) == 0
     assert J.params(64, 64).noise == 0
-    for kw in (dict(num_patches=-1), dict(num_dots=-2), dict(dot_colour_quant=(0, float("inf"), 0))):
+    for kw in (dict(num_patches=-1), dict(num_dots=-2), dict(dot_colour_quant=(0, float("inf"), 0)),
+               dict(num_splines=-1), dict(num_splines=3, num_spline_points=2),
+               dict(num_spline_points=(1 << 22) + 1), dict(num_spline_points=-1)):
         p = J.params(64, 64, **kw)
         assert J.validate_maps_host(p, f) == 7 and J.workspace_bytes(p) == 0, kw
     d = J.params(64, 64)
@@ -141,6 +144,18 @@ def test_workspace_bytes():
     # AC prediction adds its sums, 3 x 4 floats per block (13 x 7 blocks)
     extra = J.workspace_bytes(J.params(100, 50, epf_iters=0, ac_prediction=1)) - one
     assert 12 * 4 * 13 * 7 <= extra < 12 * 4 * 13 * 7 + 256
+    # dots or splines: Gaborish into a plane set of its own; splines add
+    # their curve samples (3 doubles, 16 per control point)
+    gp = J.params(100, 50, epf_iters=2, gab=1)
+    base = J.workspace_bytes(gp)
+    assert J.workspace_bytes(J.params(100, 50, epf_iters=2, gab=1, num_dots=5)) - base == xyb
+    sp = J.params(100, 50, epf_iters=2, gab=1, num_splines=3, num_spline_points=40)
+    sb = J.lib().jxlr_spline_scratch_bytes(C.byref(sp))
+    assert 3 * 16 * 8 * 40 <= sb < 3 * 16 * 8 * 40 + 256 and sb % 256 == 0
+    assert J.workspace_bytes(sp) - base == xyb + sb
+    sp0 = J.params(100, 50, epf_iters=2, gab=0, num_splines=3, num_spline_points=40)
+    assert J.workspace_bytes(sp0) - J.workspace_bytes(J.params(100, 50, epf_iters=2, gab=0)) == sb
+    assert J.lib().jxlr_spline_scratch_bytes(C.byref(gp)) == 0
 
 
 def test_batch_workspace_bytes():
@@ -159,6 +174,7 @@ def test_batch_workspace_bytes():
     assert J.batch_workspace_bytes(ps + [J.params(64, 64, noise=1)]) == 0
     assert J.batch_workspace_bytes(ps + [J.params(64, 64, num_patches=3)]) == 0
     assert J.batch_workspace_bytes(ps + [J.params(64, 64, num_dots=3)]) == 0
+    assert J.batch_workspace_bytes(ps + [J.params(64, 64, num_splines=1, num_spline_points=2)]) == 0
 
 
 # --- the library's constant tables versus the oracle's --------------------
@@ -178,6 +194,7 @@ def shim(tmp_path_factory):
     L.shim_noise_jump.restype = C.POINTER(C.c_uint64)
     L.shim_pred_sf.restype = C.c_float
     L.shim_pred_s8_1.restype = C.c_float
+    L.shim_spline_scale.restype = C.POINTER(C.c_double)
     L.shim_mul.restype = C.POINTER(C.c_int32)
     L.shim_thr.restype = C.POINTER(C.c_float)
     L.shim_mfma.restype = C.POINTER(C.c_uint16)
@@ -322,6 +339,16 @@ def _gf2_apply(rows, a, b):
         par = (bin(int(rows[r, 0]) & a).count("1") + bin(int(rows[r, 1]) & b).count("1")) & 1
         out[r >> 6] |= par << (r & 63)
     return out[0], out[1]
+
+
+def test_spline_scale_table(shim):
+    # DCTScale(k) of K.4: the oracle's ContinuousIDCT of a unit coefficient
+    # at t = -1/2, where every cosine is 1
+    got = np.ctypeslib.as_array(shim.shim_spline_scale(), shape=(32,))
+    for k in range(32):
+        e = np.zeros(32, np.float32)
+        e[k] = 1.0
+        assert got[k] == pytest.approx(O.spline_idct(e, -0.5), rel=1e-15, abs=0)
 
 
 def test_noise_jump_tables(shim):
