@@ -2336,8 +2336,12 @@ __global__ __launch_bounds__(kSplineThreads) void spline_kernel(SplineArgs a) {
     __syncthreads();
     // one wave per point: its lanes take the pixels of the footprint's
     // bounding box, so each atomic instruction adds to distinct pixels
+    // each wave a run of consecutive points, so that the group's waves add
+    // to pixels far apart along the curve at any moment
     const int cnt = min(kSplineThreads, np - base);
-    for (int i = wave; i < cnt; i += kSplineThreads / 64) {
+    const int per = (cnt + kSplineThreads / 64 - 1) / (kSplineThreads / 64);
+    const int i_end = min(cnt, (wave + 1) * per);
+    for (int i = wave * per; i < i_end; ++i) {
       const double px = s_pt[0][i], py = s_pt[1][i], amp = s_pt[2][i], sigma = s_pt[3][i];
       if (!(sigma > 0.0)) continue;  // no footprint
       const double r2 = -2.0 * sigma * sigma * kLog01;
