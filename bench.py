@@ -69,22 +69,22 @@ def log(msg):
 PMC_COPY_SCALE = {"FETCH_SIZE": 2.0, "WRITE_SIZE": 1.0}
 PMC_SOURCES = ("paper_1908_03565_amd/csrc/jxlr_kernels.hip", "paper_1908_03565_amd/csrc/jxlr_tables.cpp",
                "paper_1908_03565_amd/csrc/jxlr_tables.h", "paper_1908_03565_amd/csrc/gen_dct_consts.py")
-PMC_SOURCES_SHA256 = "91327227f92f4aea1ae7e20081335115f9465b23c55b13716ef1d79a4503a199"
+PMC_SOURCES_SHA256 = "6ef0883c52fa52b0b44fcdb4132e88089e236bc8f0b3ed009500a4c1f111ce9c"
 # (workload name, kernel) -> (FETCH_SIZE KiB, WRITE_SIZE KiB) per dispatch
 PMC_KIB = {
-    ("c2_2048x2048_mixed_epf2", "epf_kernel"): (25439.5, 49152.0),
-    ("c2_2048x2048_mixed_epf2", "recon_kernel"): (25790.4, 49481.2),
-    ("c2_2048x2048_mixed_epf2", "finish_kernel"): (24909.4, 49152.0),
-    ("c2_2048x2048_mixed_epf2_qco", "epf_kernel"): (25439.8, 49152.0),
-    ("c2_2048x2048_mixed_epf2_qco", "qco_kernel"): (70843.6, 49152.0),
-    ("c3_4096x4096_half_dct32", "epf_kernel"): (101707.3, 196608.1),
-    ("c3_4096x4096_half_dct32", "recon_kernel"): (101290.8, 197288.5),
-    ("c3_4096x4096_half_dct32", "finish_kernel"): (100388.8, 196608.0),
-    ("c4_batch64_loguniform_256_3072_epf1_u8srgb", "epf_batch_kernel"): (528688.8, 1052226.1),
-    ("c4_batch64_loguniform_256_3072_epf1_u8srgb", "recon_batch_kernel"): (536182.0, 1058003.7),
-    ("c4_batch64_loguniform_256_3072_epf1_u8srgb", "finish_batch_kernel"): (526415.0, 263651.9),
-    ("c1x1024_256x256_dct8", "recon_batch_kernel"): (401020.2, 786433.0),
-    ("c1x1024_256x256_dct8", "finish_batch_kernel"): (430138.1, 786432.0),
+    ("c2_2048x2048_mixed_epf2", "epf_kernel"): (25447.9, 49152.0),
+    ("c2_2048x2048_mixed_epf2", "recon_kernel"): (25785.2, 49481.2),
+    ("c2_2048x2048_mixed_epf2", "finish_kernel"): (24881.1, 49152.0),
+    ("c2_2048x2048_mixed_epf2_qco", "epf_kernel"): (25448.6, 49152.0),
+    ("c2_2048x2048_mixed_epf2_qco", "qco_kernel"): (70956.2, 49152.0),
+    ("c3_4096x4096_half_dct32", "epf_kernel"): (100942.5, 196608.0),
+    ("c3_4096x4096_half_dct32", "recon_kernel"): (101281.6, 197256.8),
+    ("c3_4096x4096_half_dct32", "finish_kernel"): (98968.3, 196608.0),
+    ("c4_batch64_loguniform_256_3072_epf1_u8srgb", "epf_batch_kernel"): (528696.1, 1052234.5),
+    ("c4_batch64_loguniform_256_3072_epf1_u8srgb", "recon_batch_kernel"): (536187.3, 1058629.5),
+    ("c4_batch64_loguniform_256_3072_epf1_u8srgb", "finish_batch_kernel"): (526364.3, 263614.2),
+    ("c1x1024_256x256_dct8", "recon_batch_kernel"): (401012.0, 786433.3),
+    ("c1x1024_256x256_dct8", "finish_batch_kernel"): (845796.5, 786432.0),
 }
 
 
