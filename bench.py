@@ -665,13 +665,95 @@ def bench_serving(args, J, wl, torch, np):
     }
 
 
+def bench_jpeg1(args, J, wl, torch, np):
+    """JPEG1 direct rasterization (M.6): whole-frame decodes of a 4:2:0
+    4096 x 4096 synthetic frame, then the two kernels stage by stage."""
+    j = wl.j1()
+    W, H = j["xsize"], j["ysize"]
+    jp = J.jpeg1_params(j)
+    ctx = J.Context(0)
+    coefs = ctx.jpeg1_upload(j)
+    rgb = ctx.jpeg1_empty_rgb(jp)
+    ws = ctx.jpeg1_workspace(jp)
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        ctx.jpeg1_decode(jp, coefs, rgb, ws, stream=stream)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for a, b in ev:
+        a.record(stream)
+        ctx.jpeg1_decode(jp, coefs, rgb, ws, stream=stream)
+        b.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_per_step = ev[0][0].elapsed_time(ev[-1][1]) / args.steps
+    lat = [a.elapsed_time(b) for a, b in ev]
+    mp = W * H / 1e6
+    value = mp / (ms_per_step / 1e3)
+    # stage by stage: the IDCT of every component, then the colour kernel
+    pix = [torch.empty(c.shape, dtype=torch.float32, device=c.device) for c in coefs]
+    sev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    for e in sev:
+        e[0].record(stream)
+        for c in range(len(coefs)):
+            ctx.jpeg1_idct(jp, c, coefs[c], pix[c], stream=stream)
+        e[1].record(stream)
+        ctx.jpeg1_color(jp, pix, rgb, stream=stream)
+        e[2].record(stream)
+    torch.cuda.synchronize()
+    idct_ms = statistics.mean(e[0].elapsed_time(e[1]) for e in sev)
+    color_ms = statistics.mean(e[1].elapsed_time(e[2]) for e in sev)
+    comp_px = sum(c.numel() for c in coefs)
+    idct_bytes = 8 * comp_px                               # int32 in, float out
+    color_bytes = sum(p.numel() for p in pix) * 4 + 12 * W * H  # planes in, RGB out
+    log(f"bench: jpeg1 {ms_per_step:.4f} ms/step, {value:.1f} MP/s; idct {idct_ms:.4f} ms "
+        f"({idct_bytes / idct_ms / 1e6:.0f} GB/s), colour {color_ms:.4f} ms "
+        f"({color_bytes / color_ms / 1e6:.0f} GB/s)")
+    dom, dms, dby = (("jpeg1_idct_kernel", idct_ms, idct_bytes) if idct_ms >= color_ms
+                     else ("jpeg1_color_kernel", color_ms, color_bytes))
+    roofline = dict(bound="hbm", kernel=dom, achieved=round(dby / dms / 1e6, 1),
+                    peak=HBM_PEAK_GBS, unit="GB/s", frac=round(dby / dms / 1e6 / HBM_PEAK_GBS, 4),
+                    avg_ms=round(dms, 5), algorithmic_bytes=dby, traffic=None)
+    err, cpu = None, None
+    if not args.no_check or not args.no_cpu_baseline:
+        from oracle import oracle as O
+        t = time.perf_counter()
+        ref = O.jpeg1_decode(j)
+        cpu_s = time.perf_counter() - t
+        reps = 1
+        if not args.no_cpu_baseline:
+            while cpu_s < args.cpu_seconds and reps < 1000:
+                t = time.perf_counter()
+                O.jpeg1_decode(j)
+                cpu_s += time.perf_counter() - t
+                reps += 1
+            cpu = dict(value=round(mp * reps / cpu_s, 4), unit="MP/s", cores=1, kind="oracle",
+                       sample=f"{reps} full {W}x{H} rasterization(s) in {cpu_s:.2f} s, FP64 scalar C")
+        if not args.no_check:
+            ctx.jpeg1_decode(jp, coefs, rgb, ws, stream=stream)
+            torch.cuda.synchronize()
+            e = float(np.abs(rgb.cpu().numpy() - ref).max())
+            err = dict(max_abs_err=e, tol=4e-3, scale="0..255")
+            log(f"bench: jpeg1 max-abs err {e:.3g} (tol 4e-3 on 0..255)")
+    return {"value": round(value, 2), "ms_per_step": round(ms_per_step, 5), "dtype": "f32",
+            "config": {"workload": j["name"], "xsize": W, "ysize": H, "subsampling": "4:2:0",
+                       "output": "f32 RGB 0..255", "frames_per_step": 1},
+            "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 5),
+                           "p99": round(float(np.percentile(lat, 99)), 5)},
+            "stage_ms": {"idct": round(idct_ms, 5), "colour": round(color_ms, 5)},
+            "host_wall_ms_per_step": round(wall / args.steps * 1e3, 5),
+            "error": err, "roofline": roofline, "cpu_baseline": cpu}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="c2",
-                    choices=["c1", "c2", "c2t", "c3", "c4", "c1x1024", "c5"])
+                    choices=["c1", "c2", "c2t", "c3", "c4", "c1x1024", "c5", "j1"])
     ap.add_argument("--no-check", action="store_true", help="skip the oracle comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
@@ -733,12 +815,14 @@ def main():
                           "copy_GBps": round(2 * n * 4 / ms / 1e6, 1)}))
         return
     if ((args.qco or args.acpred or args.noise or args.patches or args.dots or args.splines)
-            and args.workload in ("c4", "c1x1024", "c5")):
+            and args.workload in ("c4", "c1x1024", "c5", "j1")):
         print(json.dumps({"error": "--qco, --acpred and --noise apply to the single-frame "
                                    "workloads (the batch stages have none of them)"}))
         sys.exit(2)
     if args.workload == "c5":
         run = bench_serving
+    elif args.workload == "j1":
+        run = bench_jpeg1
     else:
         run = bench_batch if args.workload in ("c4", "c1x1024") else bench_frame
     r = run(args, J, wl, torch, np)

@@ -354,6 +354,57 @@ jxlr_status jxlr_noise_channels(jxlr_ctx* ctx, const jxlr_frame_params* p, float
 jxlr_status jxlr_finish(jxlr_ctx* ctx, const jxlr_frame_params* p, const jxlr_frame_io* io,
                         const float* xyb, size_t xyb_stride, hipStream_t stream);
 
+/* ---- JPEG1 direct rasterization (M.6) ----------------------------------------
+ * A recompressed JPEG1 frame (M.4 already decoded: quantized DCT coefficients
+ * per component and the quantization tables) straight to RGB: dequantization
+ * (M.6.1) and IDCT (M.6.2) per component, 2x linear upsampling of subsampled
+ * components (M.6.4), YCbCr -> RGB (M.6.5) and the crop (M.6.6).  Not done:
+ * the optional side channels (coefficient conditioning M.6.1.1, gated
+ * Gaborish M.6.3, HDR colour spaces M.6.5.1). */
+typedef struct {
+  int32_t xsize, ysize;       /* image size in pixels, 1..65536 */
+  int32_t num_components;     /* 1 (grey) or 3 (Y, Cb, Cr) */
+  int32_t h_samp[3], v_samp[3]; /* sampling factors 1 or 2; component 0 the largest */
+  int32_t quant[3][64];       /* quantization steps 1..65535, index 8 u + v */
+} jxlr_jpeg1_params;
+
+/* Blocks of component c: whole MCUs of 8 h_samp[0] x 8 v_samp[0] pixels
+ * cover the image, and component c has h_samp[c] x v_samp[c] blocks per MCU. */
+jxlr_status jxlr_jpeg1_blocks(const jxlr_jpeg1_params* p, int32_t c, int32_t* wib, int32_t* hib);
+
+/* Device workspace of jxlr_jpeg1_decode: one float plane per component
+ * (0 if p is invalid). */
+size_t jxlr_jpeg1_workspace_bytes(const jxlr_jpeg1_params* p);
+
+/* M.6.1-M.6.2 for component c: coef int32 [8 hib][8 wib] device memory, row
+ * stride coef_stride elements, coefficient 8 u + v of block (bx, by) at row
+ * 8 by + u, column 8 bx + v (u the vertical frequency; JPEG1's natural
+ * order); each is multiplied by quant[c][8 u + v] and I(8, u) I(8, v)
+ * (I.2.6.1) and the block goes through IDCT_2D (I.2.2).  pix: float
+ * [8 hib][8 wib], row stride pix_stride elements (a multiple of 4, the
+ * pointer 16-byte aligned), level shift not applied. */
+jxlr_status jxlr_jpeg1_idct(jxlr_ctx* ctx, const jxlr_jpeg1_params* p, int32_t c,
+                            const int32_t* coef, size_t coef_stride, float* pix, size_t pix_stride,
+                            hipStream_t stream);
+
+/* M.6.4-M.6.6: components of pix[c] (planes of jxlr_jpeg1_idct) upsampled
+ * 2x where their factor is half component 0's (horizontally first; 3/4 of
+ * the nearest sample and 1/4 of the next one out, mirrored at the plane's
+ * edges), then R = 1.402 Cr + (Y + 128), G = -0.71414 Cr - 0.34414 Cb +
+ * (Y + 128), B = 1.772 Cb + (Y + 128) (grey: all three Y + 128), cropped to
+ * xsize x ysize: rgb[3] float [ysize][xsize] with row stride rgb_stride. */
+jxlr_status jxlr_jpeg1_color(jxlr_ctx* ctx, const jxlr_jpeg1_params* p, const float* const pix[3],
+                             const size_t pix_stride[3], float* const rgb[3], size_t rgb_stride,
+                             hipStream_t stream);
+
+/* The whole rasterization: jxlr_jpeg1_idct of every component into ws, then
+ * jxlr_jpeg1_color.  coef / coef_stride as for jxlr_jpeg1_idct, per
+ * component (entries past num_components ignored). */
+jxlr_status jxlr_jpeg1_decode(jxlr_ctx* ctx, const jxlr_jpeg1_params* p,
+                              const int32_t* const coef[3], const size_t coef_stride[3],
+                              float* const rgb[3], size_t rgb_stride, void* ws, size_t ws_bytes,
+                              hipStream_t stream);
+
 /* ---- batches of frames ------------------------------------------------------
  * A batch decodes n independent frames (each with its own sizes, parameters
  * and inputs) in one launch per stage: the tiles of all frames form one list

@@ -1987,6 +1987,122 @@ int orc_quantize_srgb(int32_t bits, int64_t n, const double* lin, uint16_t* out)
 }
 
 /* ======================================================================= */
+/* JPEG1 direct rasterization (M.6)                                        */
+/* ======================================================================= */
+
+/* M.6.1 and M.6.2: one component of wib x hib blocks; qcoef int32
+ * [8 hib][8 wib], coefficient index 8 u + v of block (bx, by) at row
+ * 8 by + u, column 8 bx + v; quant[64] by the same index.  Each coefficient
+ * is multiplied by its quantization step and I(8, u) I(8, v) (I.2.6.1), then
+ * the block goes through IDCT_2D (I.2.2) with u the vertical and v the
+ * horizontal frequency (the layout of JPEG1's natural coefficient order).
+ * out: pixels [8 hib][8 wib].  The conditioning of M.6.1.1 is not applied
+ * (it is driven by an optional side channel). */
+int orc_jpeg1_component(const int32_t* qcoef, int32_t wib, int32_t hib, const int32_t* quant,
+                        double* out) {
+  if (wib < 1 || hib < 1) return ORC_E_SIZE;
+  const int32_t W = 8 * wib;
+  double T[64];
+  orc_idct_matrix(8, T);
+  for (int32_t by = 0; by < hib; ++by)
+    for (int32_t bx = 0; bx < wib; ++bx) {
+      double K[64], tmp[64];
+      for (int u = 0; u < 8; ++u)
+        for (int v = 0; v < 8; ++v)
+          K[8 * u + v] = (double)qcoef[(size_t)(8 * by + u) * W + 8 * bx + v] * quant[8 * u + v] *
+                         orc_scale_I(8, u) * orc_scale_I(8, v);
+      /* columns (vertical frequency u), then rows (horizontal frequency v) */
+      for (int y = 0; y < 8; ++y)
+        for (int v = 0; v < 8; ++v) {
+          double acc = 0.0;
+          for (int u = 0; u < 8; ++u) acc += T[y * 8 + u] * K[8 * u + v];
+          tmp[8 * y + v] = acc;
+        }
+      for (int y = 0; y < 8; ++y)
+        for (int x = 0; x < 8; ++x) {
+          double acc = 0.0;
+          for (int v = 0; v < 8; ++v) acc += T[x * 8 + v] * tmp[8 * y + v];
+          out[(size_t)(8 * by + y) * W + 8 * bx + x] = acc;
+        }
+    }
+  return ORC_OK;
+}
+
+/* M.6.4: linear 2x upsampling of n samples with respect to pixel centres,
+ * mirrored at both ends (index -1 reads index 1, index n reads n - 2):
+ * out[2i] = 3/4 a[i] + 1/4 a[i - 1], out[2i + 1] = 3/4 a[i] + 1/4 a[i + 1],
+ * with the given stride between samples (in and out). */
+void orc_upsample2(const double* in, int32_t n, size_t stride_in, double* out,
+                   size_t stride_out) {
+  for (int32_t i = 0; i < n; ++i) {
+    const int32_t l = i == 0 ? (n > 1 ? 1 : 0) : i - 1;
+    const int32_t r = i == n - 1 ? (n > 1 ? n - 2 : 0) : i + 1;
+    const double a = in[i * stride_in];
+    out[(size_t)(2 * i) * stride_out] = 0.75 * a + 0.25 * in[l * stride_in];
+    out[(size_t)(2 * i + 1) * stride_out] = 0.75 * a + 0.25 * in[r * stride_in];
+  }
+}
+
+/* M.6.4 to M.6.6: three components (Y, Cb, Cr) of pixels [8 hib_c][8 wib_c]
+ * with sampling factors hs[c], vs[c] in {1, 2} (the largest being the
+ * luma's), upsampled where a component's factor is below the largest
+ * (horizontally first), transformed to RGB by M.6.5 and cropped to xsize x
+ * ysize.  Readings: a component is upsampled over its whole block-padded
+ * plane, mirrored at that plane's edges, before the crop; one component
+ * gives grey (R = G = B = Y + 128).  rgb: [3][ysize][xsize]. */
+int orc_jpeg1_rasterize(int32_t ncomp, const double* const pix[3], const int32_t* wib,
+                        const int32_t* hib, const int32_t* hs, const int32_t* vs, int32_t xsize,
+                        int32_t ysize, double* rgb) {
+  if (ncomp != 1 && ncomp != 3) return ORC_E_PARAM;
+  if (xsize < 1 || ysize < 1) return ORC_E_SIZE;
+  int32_t hmax = 1, vmax = 1;
+  for (int c = 0; c < ncomp; ++c) {
+    if (hs[c] < 1 || hs[c] > 2 || vs[c] < 1 || vs[c] > 2) return ORC_E_PARAM;
+    if (hs[c] > hmax) hmax = hs[c];
+    if (vs[c] > vmax) vmax = vs[c];
+  }
+  double* full[3] = {NULL, NULL, NULL};
+  int st = ORC_OK;
+  for (int c = 0; c < ncomp && !st; ++c) {
+    const int32_t w = 8 * wib[c], h = 8 * hib[c];
+    const int32_t fx = hmax / hs[c], fy = vmax / vs[c];
+    if (w * fx < xsize || h * fy < ysize) { st = ORC_E_SIZE; break; }
+    double* hor = (double*)malloc(sizeof(double) * (size_t)w * fx * h);
+    full[c] = (double*)malloc(sizeof(double) * (size_t)w * fx * h * fy);
+    if (!hor || !full[c]) { free(hor); st = ORC_E_SIZE; break; }
+    for (int32_t y = 0; y < h; ++y) {
+      if (fx == 2) orc_upsample2(pix[c] + (size_t)y * w, w, 1, hor + (size_t)y * 2 * w, 1);
+      else memcpy(hor + (size_t)y * w, pix[c] + (size_t)y * w, sizeof(double) * w);
+    }
+    const int32_t W2 = w * fx;
+    for (int32_t x = 0; x < W2; ++x) {
+      if (fy == 2) orc_upsample2(hor + x, h, W2, full[c] + x, W2);
+      else for (int32_t y = 0; y < h; ++y) full[c][(size_t)y * W2 + x] = hor[(size_t)y * W2 + x];
+    }
+    free(hor);
+  }
+  if (!st) {
+    const size_t plane = (size_t)xsize * ysize;
+    for (int32_t y = 0; y < ysize; ++y)
+      for (int32_t x = 0; x < xsize; ++x) {
+        const size_t o = (size_t)y * xsize + x;
+        const double Y = full[0][(size_t)y * 8 * wib[0] * (hmax / hs[0]) + x];
+        if (ncomp == 1) {
+          rgb[o] = rgb[plane + o] = rgb[2 * plane + o] = Y + 128.0;
+          continue;
+        }
+        const double Cb = full[1][(size_t)y * 8 * wib[1] * (hmax / hs[1]) + x];
+        const double Cr = full[2][(size_t)y * 8 * wib[2] * (hmax / hs[2]) + x];
+        rgb[o] = 1.402 * Cr + (Y + 128.0);
+        rgb[plane + o] = -0.71414 * Cr - 0.34414 * Cb + (Y + 128.0);
+        rgb[2 * plane + o] = 1.772 * Cb + (Y + 128.0);
+      }
+  }
+  for (int c = 0; c < 3; ++c) free(full[c]);
+  return st;
+}
+
+/* ======================================================================= */
 /* Whole path (9.7-9.13)                                                   */
 /* ======================================================================= */
 

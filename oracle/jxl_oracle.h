@@ -28,6 +28,7 @@
 #ifndef JXL_ORACLE_H
 #define JXL_ORACLE_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -205,6 +206,21 @@ int orc_decode_features(const orc_params* p,
                         const int32_t* patch_samples, const int32_t* dots, int32_t n_dots,
                         const int32_t* spline_offsets, int32_t n_splines,
                         const int32_t* spline_points, const float* spline_dct, double* rgb);
+/* ---- JPEG1 direct rasterization (M.6) ---------------------------------- */
+/* One component: dequantization (M.6.1, without the M.6.1.1 conditioning)
+ * and IDCT_2D (M.6.2); qcoef int32 [8 hib][8 wib] in natural order per
+ * block (index 8 u + v at row 8 by + u, column 8 bx + v), quant[64];
+ * out [8 hib][8 wib]. */
+int orc_jpeg1_component(const int32_t* qcoef, int32_t wib, int32_t hib, const int32_t* quant,
+                        double* out);
+/* M.6.4 linear 2x upsampling of n samples (mirrored ends), strided. */
+void orc_upsample2(const double* in, int32_t n, size_t stride_in, double* out,
+                   size_t stride_out);
+/* M.6.4-M.6.6: upsampling, YCbCr -> RGB, crop; 1 (grey) or 3 components of
+ * pixels [8 hib][8 wib] with sampling factors 1 or 2; rgb [3][ysize][xsize]. */
+int orc_jpeg1_rasterize(int32_t ncomp, const double* const pix[3], const int32_t* wib,
+                        const int32_t* hib, const int32_t* hs, const int32_t* vs, int32_t xsize,
+                        int32_t ysize, double* rgb);
 /* Number of OpenMP threads the oracle runs with (1 when built without OpenMP). */
 int orc_num_threads(void);
 

@@ -96,6 +96,11 @@ def lib():
                                           C.c_int32, C.c_void_p, C.c_int32, C.c_void_p,
                                           C.c_void_p, _f64p]
         L.orc_dots.argtypes = [P, _i32p, C.c_int32, _f64p]
+        L.orc_jpeg1_component.argtypes = [_i32p, C.c_int32, C.c_int32, _i32p, _f64p]
+        L.orc_upsample2.argtypes = [_f64p, C.c_int32, C.c_size_t, _f64p, C.c_size_t]
+        L.orc_upsample2.restype = None
+        L.orc_jpeg1_rasterize.argtypes = [C.c_int32, C.c_void_p * 3, _i32p, _i32p, _i32p, _i32p,
+                                          C.c_int32, C.c_int32, _f64p]
         L.orc_spline_idct.argtypes = [_f32p, C.c_double]
         L.orc_spline_idct.restype = C.c_double
         L.orc_spline_curve.argtypes = [_i32p, C.c_int32, _f64p, _f64p]
@@ -394,6 +399,45 @@ def splines(p, offsets, points, dct, xyb, want_near=False):
                              d.ravel() if d.size else np.zeros(128, np.float32), out,
                              near.ctypes.data))
     return (out, near.astype(bool)) if want_near else out
+
+
+def jpeg1_component(qcoef, quant):
+    """M.6.1-M.6.2: pixels [8 hib][8 wib] of one component's quantized
+    coefficients (natural order per 8x8 block) and its quantization table."""
+    q = np.ascontiguousarray(qcoef, np.int32)
+    hib, wib = q.shape[0] // 8, q.shape[1] // 8
+    out = np.zeros(q.shape)
+    _check(lib().orc_jpeg1_component(q, wib, hib, np.ascontiguousarray(quant, np.int32).ravel(),
+                                     out))
+    return out
+
+
+def upsample2(a):
+    """M.6.4 on a 1-D array."""
+    a = np.ascontiguousarray(a, np.float64)
+    out = np.zeros(2 * len(a))
+    lib().orc_upsample2(a, len(a), 1, out, 1)
+    return out
+
+
+def jpeg1_rasterize(pixels, hs, vs, xsize, ysize):
+    """M.6.4-M.6.6: RGB (3, ysize, xsize) from 1 or 3 component planes."""
+    pl = [np.ascontiguousarray(p_, np.float64) for p_ in pixels]
+    ptrs = (C.c_void_p * 3)(*([p_.ctypes.data for p_ in pl] + [None] * (3 - len(pl))))
+    wib = np.array([p_.shape[1] // 8 for p_ in pl] + [1] * (3 - len(pl)), np.int32)
+    hib = np.array([p_.shape[0] // 8 for p_ in pl] + [1] * (3 - len(pl)), np.int32)
+    out = np.zeros((3, ysize, xsize))
+    _check(lib().orc_jpeg1_rasterize(len(pl), ptrs, wib, hib,
+                                     np.array(list(hs) + [1] * (3 - len(hs)), np.int32),
+                                     np.array(list(vs) + [1] * (3 - len(vs)), np.int32),
+                                     xsize, ysize, out))
+    return out
+
+
+def jpeg1_decode(j):
+    """Whole M.6 path of a synthetic JPEG1 frame dict (see workload.jpeg1)."""
+    pix = [jpeg1_component(c, q) for c, q in zip(j["coef"], j["quant"])]
+    return jpeg1_rasterize(pix, j["hs"], j["vs"], j["xsize"], j["ysize"])
 
 
 def splitmix64(z):

@@ -2394,6 +2394,116 @@ __global__ __launch_bounds__(kSplineThreads) void spline_kernel(SplineArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// JPEG1 direct rasterization (M.6).  jpeg1_idct_kernel: one workgroup per
+// 64x32-pixel tile of one component (8 x 4 blocks), eight threads per block.
+// Column pass: a thread takes coefficient column v of its block (the eight
+// rows of a wave's loads are 256 contiguous bytes each), multiplies by the
+// quantization steps and runs IDCT_1D with I(8, u) folded into its matrix;
+// row pass through LDS: a thread takes one pixel row of its block and stores
+// eight contiguous floats.  jpeg1_color_kernel: a thread per output pixel
+// upsamples the chroma (horizontally, then vertically, mirrored at the
+// component's plane edges), applies M.6.5 and writes the cropped RGB planes.
+
+constexpr int kJ1Threads = 256;
+
+struct J1IdctArgs {
+  const int32_t* coef;
+  size_t coef_stride;
+  float* pix;
+  size_t pix_stride;
+  int wib, hib;
+  float quant[64];  // natural order 8 u + v
+  const DeviceTables* T;
+};
+
+__global__ __launch_bounds__(kJ1Threads) void jpeg1_idct_kernel(J1IdctArgs a) {
+  __shared__ float s_tmp[32][8][9];  // [block][row y][frequency v], padded
+  __shared__ float s_a[8][8];
+  const int t = threadIdx.x;
+  const int v = t & 7, bl = t >> 3;  // frequency column / pixel row, block in tile
+  const int bx = blockIdx.x * 8 + (bl & 7), by = blockIdx.y * 4 + (bl >> 3);
+  if (t < 64) s_a[t >> 3][t & 7] = a.T->jpeg1_a[t >> 3][t & 7];
+  __syncthreads();
+  const bool live = bx < a.wib && by < a.hib;
+  if (live) {
+    float k[8];
+    const int32_t* src = a.coef + size_t(8 * by) * a.coef_stride + 8 * bx + v;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) k[u] = float(src[size_t(u) * a.coef_stride]) * a.quant[8 * u + v];
+#pragma unroll
+    for (int y = 0; y < 8; ++y) {
+      float acc = 0.0f;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc = fmaf(s_a[y][u], k[u], acc);
+      s_tmp[bl][y][v] = acc;
+    }
+  }
+  __syncthreads();
+  if (live) {
+    const int y = v;  // this thread's pixel row
+    float r[8];
+#pragma unroll
+    for (int x = 0; x < 8; ++x) {
+      float acc = 0.0f;
+#pragma unroll
+      for (int w = 0; w < 8; ++w) acc = fmaf(s_a[x][w], s_tmp[bl][y][w], acc);
+      r[x] = acc;
+    }
+    float4* dst = reinterpret_cast<float4*>(a.pix + size_t(8 * by + y) * a.pix_stride + 8 * bx);
+    dst[0] = make_float4(r[0], r[1], r[2], r[3]);
+    dst[1] = make_float4(r[4], r[5], r[6], r[7]);
+  }
+}
+
+struct J1ColorArgs {
+  int W, H, ncomp;
+  const float* pix[3];
+  size_t pix_stride[3];
+  int pw[3], ph[3];  // component plane sizes in pixels
+  int fx[3], fy[3];  // upsampling factors (1 or 2)
+  float* rgb[3];
+  size_t rgb_stride;
+};
+
+// sample (x, y) of component c at full resolution: 2x linear upsampling
+// (3/4 of the nearest sample, 1/4 of the next one out, mirrored at the
+// plane's edges), horizontally first
+__device__ inline int j1_mirror(int i, int n) {
+  return i < 0 ? (n > 1 ? 1 : 0) : (i >= n ? (n > 1 ? n - 2 : 0) : i);
+}
+__device__ inline float j1_hsample(const J1ColorArgs& a, int c, int x, int row) {
+  const float* p = a.pix[c] + size_t(row) * a.pix_stride[c];
+  if (a.fx[c] == 1) return p[x];
+  const int i = x >> 1;
+  const int o = j1_mirror((x & 1) ? i + 1 : i - 1, a.pw[c]);
+  return 0.75f * p[i] + 0.25f * p[o];
+}
+__device__ inline float j1_sample(const J1ColorArgs& a, int c, int x, int y) {
+  if (a.fy[c] == 1) return j1_hsample(a, c, x, y);
+  const int j = y >> 1;
+  const int o = j1_mirror((y & 1) ? j + 1 : j - 1, a.ph[c]);
+  return 0.75f * j1_hsample(a, c, x, j) + 0.25f * j1_hsample(a, c, x, o);
+}
+
+__global__ __launch_bounds__(kJ1Threads) void jpeg1_color_kernel(J1ColorArgs a) {
+  const int x = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
+  if (x >= a.W || y >= a.H) return;
+  const float Y = j1_sample(a, 0, x, y) + 128.0f;
+  const size_t o = size_t(y) * a.rgb_stride + x;
+  if (a.ncomp == 1) {
+    a.rgb[0][o] = Y;
+    a.rgb[1][o] = Y;
+    a.rgb[2][o] = Y;
+    return;
+  }
+  const float cb = j1_sample(a, 1, x, y), cr = j1_sample(a, 2, x, y);
+  a.rgb[0][o] = fmaf(1.402f, cr, Y);
+  a.rgb[1][o] = fmaf(-0.71414f, cr, fmaf(-0.34414f, cb, Y));
+  a.rgb[2][o] = fmaf(1.772f, cb, Y);
+}
+
+// ---------------------------------------------------------------------------
 // Noise channels (K.5.2).  One workgroup per 256x256 group and channel; each
 // thread runs one of the eight generators over 16 rows: it seeds the
 // generator (SplitMix64 chain), jumps it ahead to its first step with the
@@ -3325,6 +3435,146 @@ jxlr_status jxlr_decode(jxlr_ctx* ctx, const jxlr_frame_params* p, const jxlr_fr
       return st;
   }
   return jxlr_finish(ctx, p, &iop, cur, stride, stream);
+}
+
+}  // extern "C"
+
+// ---- JPEG1 direct rasterization (M.6) --------------------------------------
+
+namespace {
+jxlr_status j1_check(const jxlr_jpeg1_params* p) {
+  if (!p) return JXLR_E_NULL;
+  if (p->xsize < 1 || p->ysize < 1 || p->xsize > 65536 || p->ysize > 65536) return JXLR_E_SIZE;
+  if (p->num_components != 1 && p->num_components != 3) return JXLR_E_PARAM;
+  for (int c = 0; c < p->num_components; ++c) {
+    if (p->h_samp[c] < 1 || p->h_samp[c] > 2 || p->v_samp[c] < 1 || p->v_samp[c] > 2)
+      return JXLR_E_PARAM;
+    // the luma carries the largest factors
+    if (p->h_samp[c] > p->h_samp[0] || p->v_samp[c] > p->v_samp[0]) return JXLR_E_PARAM;
+    for (int i = 0; i < 64; ++i)
+      if (p->quant[c][i] < 1 || p->quant[c][i] > 65535) return JXLR_E_PARAM;
+  }
+  return JXLR_OK;
+}
+// blocks of component c: whole MCUs of (8 h_max) x (8 v_max) pixels
+void j1_blocks(const jxlr_jpeg1_params* p, int c, int* wib, int* hib) {
+  const int mx = (p->xsize + 8 * p->h_samp[0] - 1) / (8 * p->h_samp[0]);
+  const int my = (p->ysize + 8 * p->v_samp[0] - 1) / (8 * p->v_samp[0]);
+  *wib = mx * p->h_samp[c];
+  *hib = my * p->v_samp[c];
+}
+size_t j1_plane_bytes(const jxlr_jpeg1_params* p, int c) {
+  int wib, hib;
+  j1_blocks(p, c, &wib, &hib);
+  return round256(size_t(64) * wib * hib * sizeof(float));
+}
+}  // namespace
+
+extern "C" {
+
+jxlr_status jxlr_jpeg1_blocks(const jxlr_jpeg1_params* p, int32_t c, int32_t* wib, int32_t* hib) {
+  jxlr_status st = j1_check(p);
+  if (st) return st;
+  if (c < 0 || c >= p->num_components || !wib || !hib) return JXLR_E_PARAM;
+  int w, h;
+  j1_blocks(p, c, &w, &h);
+  *wib = w;
+  *hib = h;
+  return JXLR_OK;
+}
+
+size_t jxlr_jpeg1_workspace_bytes(const jxlr_jpeg1_params* p) {
+  if (j1_check(p) != JXLR_OK) return 0;
+  size_t n = 0;
+  for (int c = 0; c < p->num_components; ++c) n += j1_plane_bytes(p, c);
+  return n;
+}
+
+jxlr_status jxlr_jpeg1_idct(jxlr_ctx* ctx, const jxlr_jpeg1_params* p, int32_t c,
+                            const int32_t* coef, size_t coef_stride, float* pix, size_t pix_stride,
+                            hipStream_t stream) {
+  if (!ctx || !coef || !pix) return JXLR_E_NULL;
+  jxlr_status st = j1_check(p);
+  if (st) return st;
+  if (c < 0 || c >= p->num_components) return JXLR_E_PARAM;
+  int wib, hib;
+  j1_blocks(p, c, &wib, &hib);
+  if (coef_stride < size_t(8) * wib || pix_stride < size_t(8) * wib || pix_stride % 4 ||
+      reinterpret_cast<uintptr_t>(pix) % 16)
+    return JXLR_E_SIZE;
+  J1IdctArgs a{};
+  a.coef = coef;
+  a.coef_stride = coef_stride;
+  a.pix = pix;
+  a.pix_stride = pix_stride;
+  a.wib = wib;
+  a.hib = hib;
+  for (int i = 0; i < 64; ++i) a.quant[i] = float(p->quant[c][i]);
+  a.T = ctx->tables;
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return JXLR_E_HIP;
+  hipLaunchKernelGGL(jpeg1_idct_kernel, dim3((wib + 7) / 8, (hib + 3) / 4), dim3(kJ1Threads), 0,
+                     stream, a);
+  return launch_status(hipGetLastError());
+}
+
+jxlr_status jxlr_jpeg1_color(jxlr_ctx* ctx, const jxlr_jpeg1_params* p, const float* const pix[3],
+                             const size_t pix_stride[3], float* const rgb[3], size_t rgb_stride,
+                             hipStream_t stream) {
+  if (!ctx || !pix || !pix_stride || !rgb) return JXLR_E_NULL;
+  jxlr_status st = j1_check(p);
+  if (st) return st;
+  if (rgb_stride < size_t(p->xsize)) return JXLR_E_SIZE;
+  J1ColorArgs a{};
+  a.W = p->xsize;
+  a.H = p->ysize;
+  a.ncomp = p->num_components;
+  for (int c = 0; c < 3; ++c) {
+    if (!rgb[c]) return JXLR_E_NULL;
+    a.rgb[c] = rgb[c];
+  }
+  for (int c = 0; c < p->num_components; ++c) {
+    if (!pix[c]) return JXLR_E_NULL;
+    int wib, hib;
+    j1_blocks(p, c, &wib, &hib);
+    if (pix_stride[c] < size_t(8) * wib) return JXLR_E_SIZE;
+    a.pix[c] = pix[c];
+    a.pix_stride[c] = pix_stride[c];
+    a.pw[c] = 8 * wib;
+    a.ph[c] = 8 * hib;
+    a.fx[c] = p->h_samp[0] / p->h_samp[c];
+    a.fy[c] = p->v_samp[0] / p->v_samp[c];
+  }
+  a.rgb_stride = rgb_stride;
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return JXLR_E_HIP;
+  hipLaunchKernelGGL(jpeg1_color_kernel, dim3((p->xsize + 63) / 64, (p->ysize + 3) / 4),
+                     dim3(kJ1Threads), 0, stream, a);
+  return launch_status(hipGetLastError());
+}
+
+jxlr_status jxlr_jpeg1_decode(jxlr_ctx* ctx, const jxlr_jpeg1_params* p,
+                              const int32_t* const coef[3], const size_t coef_stride[3],
+                              float* const rgb[3], size_t rgb_stride, void* ws, size_t ws_bytes,
+                              hipStream_t stream) {
+  if (!ctx || !coef || !coef_stride || !rgb || !ws) return JXLR_E_NULL;
+  jxlr_status st = j1_check(p);
+  if (st) return st;
+  if (ws_bytes < jxlr_jpeg1_workspace_bytes(p)) return JXLR_E_WORKSPACE;
+  const float* pix[3] = {nullptr, nullptr, nullptr};
+  size_t stride[3] = {0, 0, 0};
+  char* base = static_cast<char*>(ws);
+  for (int c = 0; c < p->num_components; ++c) {
+    int wib, hib;
+    j1_blocks(p, c, &wib, &hib);
+    float* pc = reinterpret_cast<float*>(base);
+    base += j1_plane_bytes(p, c);
+    stride[c] = size_t(8) * wib;
+    if ((st = jxlr_jpeg1_idct(ctx, p, c, coef[c], coef_stride[c], pc, stride[c], stream)))
+      return st;
+    pix[c] = pc;
+  }
+  return jxlr_jpeg1_color(ctx, p, pix, stride, rgb, rgb_stride, stream);
 }
 
 }  // extern "C"

@@ -580,6 +580,12 @@ bool build_tables(DeviceTables* t) {
   t->pred_s8_1 = float(transform_scale(8, 1));
   for (int k = 0; k < 32; ++k)
     t->spline_scale[k] = scale_d(32, k) * (k == 0 ? 1.0 / (4.0 * std::sqrt(2.0)) : 0.25);
+  {
+    double t8[64];
+    inverse_transform_matrix_f64(8, t8);
+    for (int y = 0; y < 8; ++y)
+      for (int u = 0; u < 8; ++u) t->jpeg1_a[y][u] = float(t8[y * 8 + u] * scale_i(8, u));
+  }
   build_mfma_operands(t);
   for (int j = 0; j < 16; ++j)
     for (int i = 0; i < 16; ++i) t->afv[j][i] = float(kAfvBasis[j][i]);

@@ -107,6 +107,9 @@ struct DeviceTables {
   // Splines (K.4): DCTScale(k) of ContinuousIDCT, D(32, k) of I.2.6.1 times
   // 1 / (4 sqrt 2) at k = 0 and 1/4 elsewhere, in binary64.
   double spline_scale[32];
+  // JPEG1 rasterization (M.6.1-M.6.2): jpeg1_a[y][u] is IDCT_1D's entry
+  // (I.2.1) times I(8, u) (I.2.6.1), rounded once from binary64.
+  float jpeg1_a[8][8];
 };
 
 // Fills t on the host.  Returns false if a dequantization matrix entry is not

@@ -96,6 +96,23 @@ class LaunchConfig(C.Structure):
 STAGE_INFO, STAGE_RECON, STAGE_EPF, STAGE_FINISH = 0, 1, 2, 3
 
 
+class Jpeg1Params(C.Structure):
+    _fields_ = [("xsize", C.c_int32), ("ysize", C.c_int32), ("num_components", C.c_int32),
+                ("h_samp", C.c_int32 * 3), ("v_samp", C.c_int32 * 3),
+                ("quant", (C.c_int32 * 64) * 3)]
+
+
+def jpeg1_params(j):
+    """Jpeg1Params of a synthetic JPEG1 frame dict (workload.jpeg1)."""
+    p = Jpeg1Params()
+    p.xsize, p.ysize, p.num_components = j["xsize"], j["ysize"], len(j["coef"])
+    for c in range(len(j["coef"])):
+        p.h_samp[c], p.v_samp[c] = j["hs"][c], j["vs"][c]
+        for i, q in enumerate(np.asarray(j["quant"][c]).ravel()):
+            p.quant[c][i] = int(q)
+    return p
+
+
 class JxlrError(RuntimeError):
     def __init__(self, status, what=""):
         self.status = status
@@ -132,6 +149,16 @@ _SIGS = {
     "jxlr_dots": ([C.c_void_p, C.POINTER(FrameParams), C.POINTER(FrameIO), C.c_void_p, C.c_size_t,
                    C.c_void_p], C.c_int),
     "jxlr_spline_scratch_bytes": ([C.POINTER(FrameParams)], C.c_size_t),
+    "jxlr_jpeg1_blocks": ([C.c_void_p, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)],
+                          C.c_int),
+    "jxlr_jpeg1_workspace_bytes": ([C.c_void_p], C.c_size_t),
+    "jxlr_jpeg1_idct": ([C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_size_t, C.c_void_p,
+                         C.c_size_t, C.c_void_p], C.c_int),
+    "jxlr_jpeg1_color": ([C.c_void_p, C.c_void_p, C.c_void_p * 3, C.c_size_t * 3,
+                          C.c_void_p * 3, C.c_size_t, C.c_void_p], C.c_int),
+    "jxlr_jpeg1_decode": ([C.c_void_p, C.c_void_p, C.c_void_p * 3, C.c_size_t * 3,
+                           C.c_void_p * 3, C.c_size_t, C.c_void_p, C.c_size_t, C.c_void_p],
+                          C.c_int),
     "jxlr_splines": ([C.c_void_p, C.POINTER(FrameParams), C.POINTER(FrameIO), C.c_void_p,
                       C.c_size_t, C.c_void_p, C.c_size_t, C.c_void_p], C.c_int),
     "jxlr_noise_channels": ([C.c_void_p, C.POINTER(FrameParams), C.c_void_p, C.c_void_p], C.c_int),
@@ -340,6 +367,43 @@ class Context:
             pass
 
     # --- allocation helpers (torch device memory) ---
+    # --- JPEG1 direct rasterization (M.6) ---
+    def jpeg1_upload(self, j):
+        """Device copies of a synthetic JPEG1 frame's coefficient planes."""
+        import torch
+        return [torch.from_numpy(np.ascontiguousarray(c, np.int32)).to(f"cuda:{self.device}")
+                for c in j["coef"]]
+
+    def jpeg1_empty_rgb(self, jp):
+        import torch
+        return torch.empty((3, jp.ysize, jp.xsize), dtype=torch.float32,
+                           device=f"cuda:{self.device}")
+
+    def jpeg1_workspace(self, jp):
+        import torch
+        return torch.empty(max(1, lib().jxlr_jpeg1_workspace_bytes(C.byref(jp))),
+                           dtype=torch.uint8, device=f"cuda:{self.device}")
+
+    def jpeg1_idct(self, jp, c, coef, pix, stream=None):
+        _check(lib().jxlr_jpeg1_idct(self.handle, C.byref(jp), c, coef.data_ptr(), coef.shape[1],
+                                     pix.data_ptr(), pix.shape[1], _stream_handle(stream)),
+               "jpeg1_idct")
+
+    def jpeg1_color(self, jp, pix, rgb, stream=None):
+        ptr = (C.c_void_p * 3)(*([q.data_ptr() for q in pix] + [None] * (3 - len(pix))))
+        strides = (C.c_size_t * 3)(*([q.shape[1] for q in pix] + [0] * (3 - len(pix))))
+        out = (C.c_void_p * 3)(*[rgb[c].data_ptr() for c in range(3)])
+        _check(lib().jxlr_jpeg1_color(self.handle, C.byref(jp), ptr, strides, out, rgb.shape[2],
+                                      _stream_handle(stream)), "jpeg1_color")
+
+    def jpeg1_decode(self, jp, coefs, rgb, ws, stream=None):
+        ptr = (C.c_void_p * 3)(*([q.data_ptr() for q in coefs] + [None] * (3 - len(coefs))))
+        strides = (C.c_size_t * 3)(*([q.shape[1] for q in coefs] + [0] * (3 - len(coefs))))
+        out = (C.c_void_p * 3)(*[rgb[c].data_ptr() for c in range(3)])
+        _check(lib().jxlr_jpeg1_decode(self.handle, C.byref(jp), ptr, strides, out, rgb.shape[2],
+                                       ws.data_ptr(), ws.numel(), _stream_handle(stream)),
+               "jpeg1_decode")
+
     def empty_xyb(self, p):
         import torch
         return torch.empty((3, p.ysize, p.xsize), dtype=torch.float32, device=f"cuda:{self.device}")

@@ -271,6 +271,40 @@ def with_splines(f, n, seed, **kw):
     return f
 
 
+def jpeg1(W, H, seed, hs=(2, 1, 1), vs=(2, 1, 1), grey=False):
+    """A synthetic recompressed JPEG1 frame (M.4 already decoded) of W x H
+    pixels: per component the quantized coefficients int32 [8 hib][8 wib]
+    in natural order per block (whole MCUs of 8 hs[0] x 8 vs[0] pixels;
+    component c has hs[c] x vs[c] blocks per MCU), and a quantization table
+    growing with frequency (8 + 3 (u + v) for luma, 10 + 4 (u + v) for
+    chroma).  DC uniform in [-64, 63] (chroma [-24, 23]); AC Laplacian with
+    scale 6 / (1 + u + v), rounded half away from zero (most high-frequency
+    coefficients zero)."""
+    rng = np.random.default_rng(seed)
+    n = 1 if grey else 3
+    mx, my = -(-W // (8 * hs[0])), -(-H // (8 * vs[0]))
+    coef, quant = [], []
+    uu, vv = np.mgrid[0:8, 0:8]
+    for c in range(n):
+        wib, hib = mx * hs[c], my * vs[c]
+        scale = np.tile(6.0 / (1.0 + uu + vv), (hib, wib))
+        a = rng.laplace(0.0, scale)
+        q = np.sign(a) * np.floor(np.abs(a) + 0.5)
+        dc = rng.integers(-64, 64, size=(hib, wib)) if c == 0 else rng.integers(-24, 24, size=(hib, wib))
+        q[::8, ::8] = dc
+        coef.append(q.astype(np.int32))
+        quant.append((8 + 3 * (uu + vv) if c == 0 else 10 + 4 * (uu + vv)).astype(np.int32))
+    return {"xsize": W, "ysize": H, "coef": coef, "quant": quant, "hs": list(hs[:n]),
+            "vs": list(vs[:n]), "name": f"jpeg1_{W}x{H}_{'grey' if grey else 'ycbcr'}"}
+
+
+def j1():
+    """JPEG1 rasterization workload: 4096 x 4096, 4:2:0."""
+    f = jpeg1(4096, 4096, seed=9)
+    f["name"] = "j1_jpeg1_4096x4096_420"
+    return f
+
+
 def c5_mother():
     return frame(4096, 4096, seed=5, epf_iters=2, gab=1, name="c5_mother_4096x4096")
 

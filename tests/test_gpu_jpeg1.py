@@ -1,0 +1,70 @@
+"""GPU parity of JPEG1 direct rasterization (M.6): synthetic recompressed
+JPEG1 frames (4:2:0, 4:2:2, 4:4:4 and grey, ragged sizes) through the HIP
+kernels (dequantization and IDCT per component, upsampling, YCbCr -> RGB,
+crop) against the FP64 oracle, stage by stage and whole."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1908_03565_amd import workload as wl
+
+pytestmark = pytest.mark.gpu
+
+# binary32 IDCT sums of 64 products per pixel: a few ulp of the block's
+# largest dequantized coefficient (hundreds) on a 0..255 scale
+J1_TOL = 2e-3
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_1908_03565_amd import jxlr as J
+    return J.Context(0)
+
+
+CASES = [(200, 136, (2, 1, 1), (2, 1, 1), False), (131, 77, (2, 1, 1), (2, 1, 1), False),
+         (96, 72, (2, 1, 1), (1, 1, 1), False), (64, 40, (1, 1, 1), (1, 1, 1), False),
+         (75, 50, (1,), (1,), True), (1000, 24, (2, 1, 1), (2, 1, 1), False)]
+
+
+@pytest.mark.parametrize("W,H,hs,vs,grey", CASES)
+def test_jpeg1_stages_and_decode_against_oracle(ctx, W, H, hs, vs, grey):
+    import torch
+    from paper_1908_03565_amd import jxlr as J
+    j = wl.jpeg1(W, H, seed=W * 7 + H, hs=hs, vs=vs, grey=grey)
+    jp = J.jpeg1_params(j)
+    print(f"[jpeg1] {W}x{H} hs={hs} vs={vs} grey={grey}", flush=True)
+    coefs = ctx.jpeg1_upload(j)
+    pix = []
+    for c, cf in enumerate(coefs):
+        pc = torch.empty(cf.shape, dtype=torch.float32, device=cf.device)
+        ctx.jpeg1_idct(jp, c, cf, pc)
+        pix.append(pc)
+    rgb = ctx.jpeg1_empty_rgb(jp)
+    ctx.jpeg1_color(jp, pix, rgb)
+    torch.cuda.synchronize()
+    ref_pix = [O.jpeg1_component(c, q) for c, q in zip(j["coef"], j["quant"])]
+    for c in range(len(pix)):
+        err = np.abs(pix[c].cpu().numpy() - ref_pix[c]).max()
+        print("component", c, "err", err)
+        assert err <= J1_TOL
+    ref = O.jpeg1_rasterize(ref_pix, j["hs"], j["vs"], W, H)
+    got = rgb.cpu().numpy()
+    err = np.abs(got - ref).max()
+    print("rgb err", err, "range", ref.min(), ref.max())
+    assert err <= 2 * J1_TOL
+    # the whole rasterization in one call gives the same planes
+    rgb2 = ctx.jpeg1_empty_rgb(jp)
+    ctx.jpeg1_decode(jp, coefs, rgb2, ctx.jpeg1_workspace(jp))
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(rgb2.cpu().numpy(), got)
+
+
+def test_jpeg1_rejects_bad_parameters(ctx):
+    from paper_1908_03565_amd import jxlr as J
+    j = wl.jpeg1(64, 64, seed=3)
+    jp = J.jpeg1_params(j)
+    jp.v_samp[2] = 2
+    jp.v_samp[0] = 1
+    coefs = ctx.jpeg1_upload(j)
+    with pytest.raises(J.JxlrError):
+        ctx.jpeg1_decode(jp, coefs, ctx.jpeg1_empty_rgb(jp), ctx.jpeg1_workspace(J.jpeg1_params(j)))

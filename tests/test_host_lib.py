@@ -479,3 +479,36 @@ def test_footprint_covers_workspace():
     p = J.params(640, 480, epf_iters=2, out_format=2)
     fp = serving.footprint_bytes(p)
     assert fp >= J.workspace_bytes(p) + 640 * 480 * 12 + 3 * 640 * 480 * 2  # AC in, u16 out
+
+
+def test_jpeg1_params_blocks_and_workspace():
+    from paper_1908_03565_amd import workload as wl
+    j = wl.jpeg1(100, 60, 1)
+    jp = J.jpeg1_params(j)
+    got = []
+    for c in range(3):
+        w, h = C.c_int32(), C.c_int32()
+        assert J.lib().jxlr_jpeg1_blocks(C.byref(jp), c, C.byref(w), C.byref(h)) == 0
+        got.append((w.value, h.value))
+    # whole 16 x 16 MCUs over 100 x 60: 7 x 4 of them
+    assert got == [(14, 8), (7, 4), (7, 4)]
+    assert [c.shape for c in j["coef"]] == [(64, 112), (32, 56), (32, 56)]
+    ws = J.lib().jxlr_jpeg1_workspace_bytes(C.byref(jp))
+    assert ws == 112 * 64 * 4 + 2 * 56 * 32 * 4
+    bad = []
+    for field, val in (("num_components", 2), ("xsize", 0)):
+        q = J.jpeg1_params(j)
+        setattr(q, field, val)
+        bad.append(q)
+    q = J.jpeg1_params(j)
+    q.h_samp[1] = 3
+    bad.append(q)
+    q = J.jpeg1_params(j)
+    q.h_samp[1] = 2
+    q.h_samp[0] = 1  # the luma must carry the largest factors
+    bad.append(q)
+    q = J.jpeg1_params(j)
+    q.quant[2][5] = 0
+    bad.append(q)
+    for q in bad:
+        assert J.lib().jxlr_jpeg1_workspace_bytes(C.byref(q)) == 0

@@ -1203,6 +1203,67 @@ def test_splines_follow_dots_and_precede_noise():
 
 
 # --------------------------------------------------------------------------
+# JPEG1 direct rasterization (M.6)
+# --------------------------------------------------------------------------
+
+def test_jpeg1_upsampling_worked_example():
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "jpeg1_upsample_example.txt")
+    rows = [list(map(float, l.split())) for l in open(path) if l.strip() and not l.startswith("#")]
+    np.testing.assert_array_equal(O.upsample2(rows[0]), rows[1])
+
+
+def test_jpeg1_component_is_the_orthonormal_idct_of_the_dequantized_block():
+    import scipy.fft as sf
+    from paper_1908_03565_amd import workload as wl
+    j = wl.jpeg1(40, 24, seed=190, hs=(1, 1, 1), vs=(1, 1, 1), grey=True)
+    q, quant = j["coef"][0], j["quant"][0]
+    pix = O.jpeg1_component(q, quant)
+    for by in range(q.shape[0] // 8):
+        for bx in range(q.shape[1] // 8):
+            blk = q[8 * by:8 * by + 8, 8 * bx:8 * bx + 8] * quant
+            # JPEG's inverse DCT: (1/4) C(u) C(v) sum ... = scipy's DCT-III, ortho
+            want = sf.idctn(blk.astype(float), type=2, norm="ortho")
+            np.testing.assert_allclose(pix[8 * by:8 * by + 8, 8 * bx:8 * bx + 8], want, atol=1e-10)
+    # coefficient 8 u + v with u = 0, v = 1: a horizontal cosine, constant down columns
+    one = np.zeros((8, 8), np.int32)
+    one[0, 1] = 10
+    p1 = O.jpeg1_component(one, np.ones(64, np.int32))
+    assert np.ptp(p1, axis=0).max() < 1e-12 and np.ptp(p1[0]) > 1.0
+
+
+def test_jpeg1_colour_transform_inverts_the_jfif_forward_matrix():
+    # the printed constants are the JFIF forward transform's inverse to five digits
+    fwd = np.array([[0.299, 0.587, 0.114], [-0.168736, -0.331264, 0.5], [0.5, -0.418688, -0.081312]])
+    rng = _rng(191)
+    planes = [rng.uniform(-100, 100, size=(8, 8)) for _ in range(3)]
+    rgb = O.jpeg1_rasterize(planes, (1, 1, 1), (1, 1, 1), 8, 8)
+    ycc = np.stack(planes).reshape(3, -1)
+    want = (np.linalg.inv(fwd) @ ycc).reshape(3, 8, 8) + 128.0
+    np.testing.assert_allclose(rgb, want, atol=2e-3)
+    grey = O.jpeg1_rasterize(planes[:1], (1,), (1,), 8, 8)
+    for c in range(3):
+        np.testing.assert_allclose(grey[c], planes[0] + 128.0, atol=0)
+
+
+def test_jpeg1_420_upsampling_keeps_linear_ramps_and_crops():
+    # chroma planes that are linear ramps come back as linear ramps at full
+    # resolution (bilinear weights) away from the mirrored edges
+    Wc, Hc = 16, 8
+    yy, xx = np.mgrid[0:Hc, 0:Wc]
+    cb = 2.0 * xx + 0.5 * yy
+    luma = np.zeros((2 * Hc, 2 * Wc))
+    rgb = O.jpeg1_rasterize([luma, cb, np.zeros_like(cb)], (2, 1, 1), (2, 1, 1), 2 * Wc - 3,
+                            2 * Hc - 5)
+    assert rgb.shape == (3, 2 * Hc - 5, 2 * Wc - 3)
+    got_cb = (rgb[2] - 128.0) / 1.772
+    Y, X = np.mgrid[0:2 * Hc - 5, 0:2 * Wc - 3]
+    want = 2.0 * (X - 0.5) / 2 + 0.5 * (Y - 0.5) / 2  # sample centres of the half grid
+    inner = (X >= 1) & (X < 2 * Wc - 3) & (Y >= 1)
+    np.testing.assert_allclose(got_cb[inner], want[inner], atol=1e-12)
+
+
+# --------------------------------------------------------------------------
 # Noise (K.5)
 # --------------------------------------------------------------------------
 
