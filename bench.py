@@ -69,22 +69,23 @@ def log(msg):
 PMC_COPY_SCALE = {"FETCH_SIZE": 2.0, "WRITE_SIZE": 1.0}
 PMC_SOURCES = ("paper_1908_03565_amd/csrc/jxlr_kernels.hip", "paper_1908_03565_amd/csrc/jxlr_tables.cpp",
                "paper_1908_03565_amd/csrc/jxlr_tables.h", "paper_1908_03565_amd/csrc/gen_dct_consts.py")
-PMC_SOURCES_SHA256 = "6ef0883c52fa52b0b44fcdb4132e88089e236bc8f0b3ed009500a4c1f111ce9c"
+PMC_SOURCES_SHA256 = "5cd1a9bfed1b3cacae154e1da62715c0727f10cb584adaa8f7dc569da7203fa6"
 # (workload name, kernel) -> (FETCH_SIZE KiB, WRITE_SIZE KiB) per dispatch
 PMC_KIB = {
-    ("c2_2048x2048_mixed_epf2", "epf_kernel"): (25447.9, 49152.0),
-    ("c2_2048x2048_mixed_epf2", "recon_kernel"): (25785.2, 49481.2),
-    ("c2_2048x2048_mixed_epf2", "finish_kernel"): (24881.1, 49152.0),
-    ("c2_2048x2048_mixed_epf2_qco", "epf_kernel"): (25448.6, 49152.0),
-    ("c2_2048x2048_mixed_epf2_qco", "qco_kernel"): (70956.2, 49152.0),
-    ("c3_4096x4096_half_dct32", "epf_kernel"): (100942.5, 196608.0),
-    ("c3_4096x4096_half_dct32", "recon_kernel"): (101281.6, 197256.8),
-    ("c3_4096x4096_half_dct32", "finish_kernel"): (98968.3, 196608.0),
-    ("c4_batch64_loguniform_256_3072_epf1_u8srgb", "epf_batch_kernel"): (528696.1, 1052234.5),
-    ("c4_batch64_loguniform_256_3072_epf1_u8srgb", "recon_batch_kernel"): (536187.3, 1058629.5),
-    ("c4_batch64_loguniform_256_3072_epf1_u8srgb", "finish_batch_kernel"): (526364.3, 263614.2),
-    ("c1x1024_256x256_dct8", "recon_batch_kernel"): (401012.0, 786433.3),
-    ("c1x1024_256x256_dct8", "finish_batch_kernel"): (845796.5, 786432.0),
+    ("c2_2048x2048_mixed_epf2", "epf_kernel"): (25446.8, 49152.0),
+    ("c2_2048x2048_mixed_epf2", "recon_kernel"): (25791.9, 49481.2),
+    ("c2_2048x2048_mixed_epf2", "finish_kernel"): (24850.1, 49152.0),
+    ("c2_2048x2048_mixed_epf2_qco", "epf_kernel"): (25447.1, 49152.0),
+    ("c2_2048x2048_mixed_epf2_qco", "qco_kernel"): (70959.0, 49152.0),
+    ("c3_4096x4096_half_dct32", "epf_kernel"): (101214.2, 196608.0),
+    ("c3_4096x4096_half_dct32", "recon_kernel"): (101291.7, 197254.5),
+    ("c3_4096x4096_half_dct32", "finish_kernel"): (98846.3, 196608.0),
+    ("c4_batch64_loguniform_256_3072_epf1_u8srgb", "epf_batch_kernel"): (528697.5, 1052229.0),
+    ("c4_batch64_loguniform_256_3072_epf1_u8srgb", "recon_batch_kernel"): (536213.5, 1059137.4),
+    ("c4_batch64_loguniform_256_3072_epf1_u8srgb", "finish_batch_kernel"): (526371.2, 263626.3),
+    ("c1x1024_256x256_dct8", "recon_batch_kernel"): (401024.0, 786434.0),
+    ("c1x1024_256x256_dct8", "finish_batch_kernel"): (845191.4, 786432.0),
+    ("j1_jpeg1_4096x4096_420", "jpeg1_color_kernel"): (81439.2, 196608.0),
 }
 
 
@@ -715,7 +716,8 @@ def bench_jpeg1(args, J, wl, torch, np):
                      else ("jpeg1_color_kernel", color_ms, color_bytes))
     roofline = dict(bound="hbm", kernel=dom, achieved=round(dby / dms / 1e6, 1),
                     peak=HBM_PEAK_GBS, unit="GB/s", frac=round(dby / dms / 1e6 / HBM_PEAK_GBS, 4),
-                    avg_ms=round(dms, 5), algorithmic_bytes=dby, traffic=None)
+                    avg_ms=round(dms, 5), algorithmic_bytes=dby,
+                    traffic=traffic_bytes(j["name"], dom))
     err, cpu = None, None
     if not args.no_check or not args.no_cpu_baseline:
         from oracle import oracle as O
