@@ -2485,22 +2485,31 @@ __device__ inline float j1_sample(const J1ColorArgs& a, int c, int x, int y) {
   return 0.75f * j1_hsample(a, c, x, j) + 0.25f * j1_hsample(a, c, x, o);
 }
 
+// A workgroup covers 64 x 16 output pixels, each wave four consecutive rows
+// (a 4:2:0 tile then reads 10 chroma rows for 8 of its own, where 64 x 4
+// tiles read 4 for 2).
+constexpr int kJ1Rows = 4;
+
 __global__ __launch_bounds__(kJ1Threads) void jpeg1_color_kernel(J1ColorArgs a) {
   const int x = blockIdx.x * 64 + (threadIdx.x & 63);
-  const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
-  if (x >= a.W || y >= a.H) return;
-  const float Y = j1_sample(a, 0, x, y) + 128.0f;
-  const size_t o = size_t(y) * a.rgb_stride + x;
-  if (a.ncomp == 1) {
-    a.rgb[0][o] = Y;
-    a.rgb[1][o] = Y;
-    a.rgb[2][o] = Y;
-    return;
+  const int y0 = blockIdx.y * (kJ1Threads / 64 * kJ1Rows) + (threadIdx.x >> 6) * kJ1Rows;
+  if (x >= a.W) return;
+  for (int r = 0; r < kJ1Rows; ++r) {
+    const int y = y0 + r;
+    if (y >= a.H) return;
+    const float Y = j1_sample(a, 0, x, y) + 128.0f;
+    const size_t o = size_t(y) * a.rgb_stride + x;
+    if (a.ncomp == 1) {
+      a.rgb[0][o] = Y;
+      a.rgb[1][o] = Y;
+      a.rgb[2][o] = Y;
+      continue;
+    }
+    const float cb = j1_sample(a, 1, x, y), cr = j1_sample(a, 2, x, y);
+    a.rgb[0][o] = fmaf(1.402f, cr, Y);
+    a.rgb[1][o] = fmaf(-0.71414f, cr, fmaf(-0.34414f, cb, Y));
+    a.rgb[2][o] = fmaf(1.772f, cb, Y);
   }
-  const float cb = j1_sample(a, 1, x, y), cr = j1_sample(a, 2, x, y);
-  a.rgb[0][o] = fmaf(1.402f, cr, Y);
-  a.rgb[1][o] = fmaf(-0.71414f, cr, fmaf(-0.34414f, cb, Y));
-  a.rgb[2][o] = fmaf(1.772f, cb, Y);
 }
 
 // ---------------------------------------------------------------------------
@@ -3548,7 +3557,8 @@ jxlr_status jxlr_jpeg1_color(jxlr_ctx* ctx, const jxlr_jpeg1_params* p, const fl
   a.rgb_stride = rgb_stride;
   DeviceGuard g(ctx->device);
   if (!g.ok) return JXLR_E_HIP;
-  hipLaunchKernelGGL(jpeg1_color_kernel, dim3((p->xsize + 63) / 64, (p->ysize + 3) / 4),
+  const int rows = kJ1Threads / 64 * kJ1Rows;
+  hipLaunchKernelGGL(jpeg1_color_kernel, dim3((p->xsize + 63) / 64, (p->ysize + rows - 1) / rows),
                      dim3(kJ1Threads), 0, stream, a);
   return launch_status(hipGetLastError());
 }
