@@ -69,23 +69,23 @@ def log(msg):
 PMC_COPY_SCALE = {"FETCH_SIZE": 2.0, "WRITE_SIZE": 1.0}
 PMC_SOURCES = ("paper_1908_03565_amd/csrc/jxlr_kernels.hip", "paper_1908_03565_amd/csrc/jxlr_tables.cpp",
                "paper_1908_03565_amd/csrc/jxlr_tables.h", "paper_1908_03565_amd/csrc/gen_dct_consts.py")
-PMC_SOURCES_SHA256 = "5cd1a9bfed1b3cacae154e1da62715c0727f10cb584adaa8f7dc569da7203fa6"
+PMC_SOURCES_SHA256 = "886202c6a800b9b191c27a88b0aeb744bb6ff545e511341d665c54ca7d32d7b4"
 # (workload name, kernel) -> (FETCH_SIZE KiB, WRITE_SIZE KiB) per dispatch
 PMC_KIB = {
-    ("c2_2048x2048_mixed_epf2", "epf_kernel"): (25446.8, 49152.0),
-    ("c2_2048x2048_mixed_epf2", "recon_kernel"): (25791.9, 49481.2),
-    ("c2_2048x2048_mixed_epf2", "finish_kernel"): (24850.1, 49152.0),
-    ("c2_2048x2048_mixed_epf2_qco", "epf_kernel"): (25447.1, 49152.0),
-    ("c2_2048x2048_mixed_epf2_qco", "qco_kernel"): (70959.0, 49152.0),
-    ("c3_4096x4096_half_dct32", "epf_kernel"): (101214.2, 196608.0),
-    ("c3_4096x4096_half_dct32", "recon_kernel"): (101291.7, 197254.5),
-    ("c3_4096x4096_half_dct32", "finish_kernel"): (98846.3, 196608.0),
-    ("c4_batch64_loguniform_256_3072_epf1_u8srgb", "epf_batch_kernel"): (528697.5, 1052229.0),
-    ("c4_batch64_loguniform_256_3072_epf1_u8srgb", "recon_batch_kernel"): (536213.5, 1059137.4),
-    ("c4_batch64_loguniform_256_3072_epf1_u8srgb", "finish_batch_kernel"): (526371.2, 263626.3),
-    ("c1x1024_256x256_dct8", "recon_batch_kernel"): (401024.0, 786434.0),
-    ("c1x1024_256x256_dct8", "finish_batch_kernel"): (845191.4, 786432.0),
-    ("j1_jpeg1_4096x4096_420", "jpeg1_color_kernel"): (81439.2, 196608.0),
+    ("c2_2048x2048_mixed_epf2", "epf_kernel"): (25440.3, 49152.0),
+    ("c2_2048x2048_mixed_epf2", "recon_kernel"): (25801.9, 49481.5),
+    ("c2_2048x2048_mixed_epf2", "finish_kernel"): (24867.1, 49152.0),
+    ("c2_2048x2048_mixed_epf2_qco", "epf_kernel"): (25440.6, 49152.0),
+    ("c2_2048x2048_mixed_epf2_qco", "qco_kernel"): (70739.9, 49152.0),
+    ("c3_4096x4096_half_dct32", "epf_kernel"): (100875.2, 196608.0),
+    ("c3_4096x4096_half_dct32", "recon_kernel"): (101301.6, 197260.8),
+    ("c3_4096x4096_half_dct32", "finish_kernel"): (98837.1, 196608.0),
+    ("c4_batch64_loguniform_256_3072_epf1_u8srgb", "epf_batch_kernel"): (528696.7, 1052232.7),
+    ("c4_batch64_loguniform_256_3072_epf1_u8srgb", "recon_batch_kernel"): (536225.3, 1058823.5),
+    ("c4_batch64_loguniform_256_3072_epf1_u8srgb", "finish_batch_kernel"): (526417.4, 263633.5),
+    ("c1x1024_256x256_dct8", "recon_batch_kernel"): (401017.1, 786433.2),
+    ("c1x1024_256x256_dct8", "finish_batch_kernel"): (845682.8, 786432.0),
+    ("j1_jpeg1_4096x4096_420", "jpeg1_color_kernel"): (81728.7, 196608.0),
 }
 
 
