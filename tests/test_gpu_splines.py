@@ -153,3 +153,27 @@ def test_ill_formed_splines_are_skipped_with_the_flag(ctx):
     want2 = O.splines(O.params(W, H), o[:-1], good["spline_points"][:o[-2]],
                       good["spline_dct"][:5], base)
     assert np.abs(got2 - want2).max() <= SPLINE_TOL * max(1.0, float(np.abs(want2).max()))
+
+
+def test_splines_with_non_positive_sigma_add_nothing_there(ctx):
+    # sigma falls below zero along part of the spline: those points add
+    # nothing, the rest as the oracle
+    from paper_1908_03565_amd import jxlr as J
+    W, H = 120, 64
+    f = dict(wl.small(W, H, seed=192, epf_iters=0))
+    f["spline_offsets"] = np.array([0, 3, 4], np.int32)
+    f["spline_points"] = np.array([[5, 30], [60, 10], [115, 40], [60, 50]], np.int32)
+    d = np.zeros((2, 4, 32), np.float32)
+    d[:, :3, 0] = [[6.0, 9.0, -3.0], [2.0, 4.0, 1.0]]
+    d[0, 3, 0], d[0, 3, 1] = 16.0, 40.0  # sigma from about 3 down through 0 to -2
+    d[1, 3, 0] = -32.0                   # a single point with sigma -1
+    f["spline_dct"] = d
+    p = J.params(W, H, num_splines=2, num_spline_points=4)
+    base = np.zeros((3, H, W), np.float32)
+    got = _stage(ctx, p, f, base)
+    assert ctx.device_status() == 0
+    want = O.splines(O.params(W, H), f["spline_offsets"], f["spline_points"], d, base)
+    assert np.abs(got - want).max() <= SPLINE_TOL * max(1.0, float(np.abs(want).max()))
+    assert np.abs(want).max() > 0.05
+    # the right end (sigma <= 0) and the single point leave the frame as it was
+    assert not want[:, :, 100:].any() and not want[:, 45:56, 55:66].any()

@@ -1181,6 +1181,15 @@ def test_spline_values_follow_the_arc_length():
     assert abs(out[0, y0, x0] - out[0, y0, x1]) > 0.01
 
 
+def test_spline_points_without_positive_sigma_add_nothing():
+    W, H = 40, 30
+    d = _spline_dct((0.5, 1.0, -0.5), -1.5)[None]
+    out = O.splines(O.params(W, H), [0, 2], [[5, 5], [30, 20]], d, np.zeros((3, H, W)))
+    assert not out.any()
+    d[0, 3, 0] = 0.0
+    assert not O.splines(O.params(W, H), [0, 2], [[5, 5], [30, 20]], d, np.zeros((3, H, W))).any()
+
+
 def test_splines_follow_dots_and_precede_noise():
     W, H = 40, 24
     f = _frame_of(0, W, H, _rng(170).integers(-200, 200, size=(3, 3, 5)),
