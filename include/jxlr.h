@@ -360,7 +360,14 @@ jxlr_status jxlr_finish(jxlr_ctx* ctx, const jxlr_frame_params* p, const jxlr_fr
  * (M.6.1) and IDCT (M.6.2) per component, 2x linear upsampling of subsampled
  * components (M.6.4), YCbCr -> RGB (M.6.5) and the crop (M.6.6).  Not done:
  * the optional side channels (coefficient conditioning M.6.1.1, gated
- * Gaborish M.6.3, HDR colour spaces M.6.5.1). */
+ * Gaborish M.6.3, HDR colour spaces M.6.5.1).  Errors, all synchronous and
+ * before any launch: JXLR_E_NULL for a missing pointer; JXLR_E_PARAM for a
+ * component count other than 1 or 3, a sampling factor outside {1, 2} or
+ * above component 0's, a quantization step outside 1..65535 or a component
+ * index out of range; JXLR_E_SIZE for sizes outside 1..65536 or strides
+ * below a plane's width (and, for pix, not a multiple of 4 or not 16-byte
+ * aligned); JXLR_E_WORKSPACE for a workspace below
+ * jxlr_jpeg1_workspace_bytes.  All buffers are the caller's device memory. */
 typedef struct {
   int32_t xsize, ysize;       /* image size in pixels, 1..65536 */
   int32_t num_components;     /* 1 (grey) or 3 (Y, Cb, Cr) */
