@@ -1805,16 +1805,30 @@ uint64_t orc_splitmix64(uint64_t z) {
   return z;
 }
 
+/* K.5.2: one XorShift128+ step of one generator on its state (s0, s1), in
+ * place; returns batch[i].  Reading: the printed step updates s1 only; a
+ * XorShift128+ step also moves the old second word into the first place, so
+ * after it s1 takes the old s0 and s0 the updated value (without the
+ * exchange s0 would never change). */
+uint64_t orc_noise_step(uint64_t* s0, uint64_t* s1) {
+  /* the printed step, then the two state words change places (s1 the first
+   * word, s0 the second) */
+  const uint64_t t = *s0;
+  *s1 ^= *s1 << 23;
+  const uint64_t b = *s1 + *s0;
+  *s1 ^= *s0 ^ (*s1 >> 18) ^ (*s0 >> 5);
+  *s0 = *s1;
+  *s1 = t;
+  return b;
+}
+
 /* K.5.2: the three pseudorandom channels RR, RG, RB of the group whose
  * top-left pixel is (x0, y0), gw x gh samples each: eight XorShift128+
  * generators seeded from (y0 << 32) + x0 through SplitMix64; per row and per
  * segment of up to 16 samples one step of all eight gives sixteen 32-bit
  * words, sample j of the segment being the binary32 with exponent 0 and the
  * top 23 bits of word j as mantissa, minus 1.  Channels, rows and segments
- * follow in that order from one generator state.  Reading: the printed step
- * updates s1 only; a XorShift128+ step also moves the old second word into
- * the first place, so after it s1 takes the old s0 and s0 the updated value
- * (without the exchange s0 would never change).  out: [3][gh][gw]. */
+ * follow in that order from one generator state.  out: [3][gh][gw]. */
 void orc_noise_channels(int32_t gw, int32_t gh, int32_t x0, int32_t y0, float* out) {
   uint64_t s0[8], s1[8];
   const uint64_t seed = ((uint64_t)(uint32_t)y0 << 32) + (uint64_t)(uint32_t)x0;
@@ -1829,14 +1843,7 @@ void orc_noise_channels(int32_t gw, int32_t gh, int32_t x0, int32_t y0, float* o
       for (int32_t x = 0; x < gw; x += 16) {
         uint32_t bits[16];
         for (int i = 0; i < 8; ++i) {
-          /* one XorShift128+ step of generator i, as printed, then the two
-           * state words change places (s1 the first word, s0 the second) */
-          const uint64_t t = s0[i];
-          s1[i] ^= s1[i] << 23;
-          const uint64_t b = s1[i] + s0[i];
-          s1[i] ^= s0[i] ^ (s1[i] >> 18) ^ (s0[i] >> 5);
-          s0[i] = s1[i];
-          s1[i] = t;
+          const uint64_t b = orc_noise_step(&s0[i], &s1[i]);
           bits[2 * i] = (uint32_t)b;
           bits[2 * i + 1] = (uint32_t)(b >> 32);
         }

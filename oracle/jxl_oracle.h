@@ -172,6 +172,9 @@ int orc_splines(const orc_params* p, const int32_t* offsets, int32_t n, const in
 /* K.5.2 SplitMix64 and the three pseudorandom channels [3][gh][gw] of the
  * group with top-left pixel (x0, y0). */
 uint64_t orc_splitmix64(uint64_t z);
+/* One step of one of the eight XorShift128+ generators of K.5.2 on its state
+ * (s0, s1), in place; returns batch[i] of that step. */
+uint64_t orc_noise_step(uint64_t* s0, uint64_t* s1);
 void orc_noise_channels(int32_t gw, int32_t gh, int32_t x0, int32_t y0, float* out);
 /* K.5 noise over a cropped XYB frame (applied after Gaborish). */
 int orc_noise(const orc_params* p, const double* in, double* out);

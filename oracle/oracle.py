@@ -88,6 +88,8 @@ def lib():
         L.orc_gaborish.argtypes = [P, _f64p, _f64p]
         L.orc_splitmix64.argtypes = [C.c_uint64]
         L.orc_splitmix64.restype = C.c_uint64
+        L.orc_noise_step.argtypes = [C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)]
+        L.orc_noise_step.restype = C.c_uint64
         L.orc_noise_channels.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.c_int32, _f32p]
         L.orc_noise.argtypes = [P, _f64p, _f64p]
         L.orc_patches.argtypes = [P, _i32p, C.c_int32, _i32p, _f64p]
@@ -442,6 +444,13 @@ def jpeg1_decode(j):
 
 def splitmix64(z):
     return lib().orc_splitmix64(int(z) & (2**64 - 1))
+
+
+def noise_step(s0, s1):
+    """One K.5.2 generator step on the state (s0, s1): returns (batch, s0', s1')."""
+    a, b = C.c_uint64(int(s0) & (2**64 - 1)), C.c_uint64(int(s1) & (2**64 - 1))
+    out = lib().orc_noise_step(C.byref(a), C.byref(b))
+    return int(out), int(a.value), int(b.value)
 
 
 def noise_channels(gw, gh, x0, y0):

@@ -1328,6 +1328,80 @@ def test_noise_channels_are_uniform_23_bit_samples():
     assert np.abs(small[0, 1] - ch[0, 1, :16]).max() > 0.1
 
 
+# Prime factors of 2^128 - 1 = (2^64 + 1)(2^32 + 1)(2^16 + 1)(2^8 + 1)(2^4 + 1)(2^2 + 1)(2 + 1).
+_ORDER_PRIMES = [3, 5, 17, 257, 641, 65537, 274177, 6700417, 67280421310721]
+
+
+def _gf2_step_matrix():
+    """The 128 x 128 matrix over GF(2) of one generator step, state bits
+    0-63 = s0 and 64-127 = s1, built column by column from the oracle's step
+    applied to the unit states (the step is linear over GF(2))."""
+    M = np.zeros((128, 128), np.uint8)
+    for j in range(128):
+        s0, s1 = (1 << j, 0) if j < 64 else (0, 1 << (j - 64))
+        _, a, b = O.noise_step(s0, s1)
+        v = a | (b << 64)
+        M[:, j] = [(v >> r) & 1 for r in range(128)]
+    return M
+
+
+def _gf2_mul(A, B):
+    return (A.astype(np.float64) @ B.astype(np.float64) % 2.0).astype(np.uint8)
+
+
+def _gf2_pow(sq, e):
+    """M^e from the repeated squares sq[k] = M^(2^k)."""
+    R = np.eye(128, dtype=np.uint8)
+    k = 0
+    while e:
+        if e & 1:
+            R = _gf2_mul(R, sq[k])
+        e >>= 1
+        k += 1
+    return R
+
+
+def test_noise_step_is_a_full_period_xorshift():
+    # K.5.2 names its generator XorShift128+: a linear map of the 128-bit
+    # state of maximal period, so its matrix over GF(2) has order exactly
+    # 2^128 - 1.  This holds for the generator's full-period shift triple
+    # and fails for a wrong shift or a step that leaves one word unchanged
+    # (as the printed step taken without the exchange of the two words does).
+    n = 2 ** 128 - 1
+    assert math.prod(_ORDER_PRIMES) == n
+    M = _gf2_step_matrix()
+    # linearity: the step of a sum of states is the sum of the steps
+    rng = _rng(7)
+    for _ in range(4):
+        a0, a1, b0, b1 = (int(v) for v in rng.integers(0, 2 ** 63, size=4, dtype=np.int64))
+        _, x0, x1 = O.noise_step(a0, a1)
+        _, y0, y1 = O.noise_step(b0, b1)
+        _, z0, z1 = O.noise_step(a0 ^ b0, a1 ^ b1)
+        assert (z0, z1) == (x0 ^ y0, x1 ^ y1)
+    sq = [M]
+    for _ in range(128):
+        sq.append(_gf2_mul(sq[-1], sq[-1]))
+    I = np.eye(128, dtype=np.uint8)
+    assert np.array_equal(sq[128], M)  # M^(2^128) = M, so M^n = I
+    assert np.array_equal(_gf2_pow(sq, n), I)
+    for q in _ORDER_PRIMES:
+        assert not np.array_equal(_gf2_pow(sq, n // q), I), q
+
+
+def test_noise_step_output_is_the_sum_of_the_shifted_word_and_the_other():
+    # batch[i] of K.5.2 is a sum modulo 2^64 of two words of the state, so
+    # its lowest bit is linear: the xor of the two words' lowest bits (the
+    # shift by 23 leaves bit 0 alone), and its carry-free low 23 bits equal
+    # the xor of s0's with s1's when s0's low 23 bits are zero
+    rng = _rng(8)
+    for _ in range(20):
+        s0, s1 = (int(v) for v in rng.integers(0, 2 ** 63, size=2, dtype=np.int64))
+        b, _, _ = O.noise_step(s0, s1)
+        assert (b & 1) == ((s0 ^ s1) & 1)
+        b2, _, _ = O.noise_step(s0 & ~((1 << 23) - 1), s1)
+        assert (b2 & ((1 << 23) - 1)) == (s1 & ((1 << 23) - 1))
+
+
 def _noise_A(gw, gh, x0, y0):
     ch = O.noise_channels(gw, gh, x0, y0).astype(np.float64)
     k = np.zeros((5, 5))
