@@ -777,7 +777,7 @@ static double interpolate(double pos, double maxv, const double* bands, int len)
  * loop writes index i + 1 and would leave index 1 unset). */
 static void dct_weights(int X, int Y, const double* db, int nb, const double* eb, int ne,
                         double* w) {
-  double dbands[16], ebands[16];
+  double dbands[17], ebands[9];
   dbands[0] = db[0];
   for (int i = 1; i < nb; ++i) dbands[i] = dbands[i - 1] * band_factor(db[i]);
   ebands[0] = 1.0;
@@ -795,118 +795,207 @@ static void dct_weights(int X, int Y, const double* db, int nb, const double* eb
     }
 }
 
-int orc_dequant_matrix(int s, int c, double* out) {
-  int32_t bx, by;
-  if (!supported(s) || !orc_varblock_size(s, &bx, &by)) return ORC_E_STRATEGY;
-  if (c < 0 || c > 2) return ORC_E_PARAM;
-  double w[32 * 32], num[32 * 32];
-  int X = bx, Y = by;
-  if (s == ORC_IDENTITY) {
-    for (int i = 0; i < 64; ++i) w[i] = P_IDENTITY[c][0];
-    w[0 * 8 + 1] = w[1 * 8 + 0] = P_IDENTITY[c][1];
-    w[1 * 8 + 1] = P_IDENTITY[c][2];
-    for (int i = 0; i < 64; ++i) num[i] = 1.0;
-  } else if (s == ORC_DCT2) {
+/* C.6.1.1: the default encoding of each transform type's matrix (the mode
+ * the defaults are given in, and their parameters). */
+int orc_default_encoding(int s, orc_dequant_encoding* e) {
+  if (!supported(s)) return ORC_E_STRATEGY;
+  memset(e, 0, sizeof(*e));
+  const double* db = NULL;
+  const double* eb = NULL;
+  int nb = 0, ne = 0;
+  for (int c = 0; c < 3; ++c) {
+    switch (s) {
+      case ORC_IDENTITY:
+        e->mode = ORC_DQ_IDENTITY;
+        for (int i = 0; i < 3; ++i) e->params[c][i] = P_IDENTITY[c][i];
+        continue;
+      case ORC_DCT2:
+        e->mode = ORC_DQ_DCT2;
+        for (int i = 0; i < 6; ++i) e->params[c][i] = P_DCT2[c][i];
+        continue;
+      case ORC_AFV:
+        e->mode = ORC_DQ_AFV;
+        for (int i = 0; i < 8; ++i) e->afv_weights[c][i] = AFV_W[c][i];
+        e->params[c][0] = AFV_P[c][0];
+        e->params[c][1] = AFV_P[c][1];
+        continue;
+      case ORC_DCT4:
+        e->mode = ORC_DQ_DCT4;
+        db = DB_DCT4[c]; nb = 4; ne = 2;
+        e->params[c][0] = P_DCT4[c][0];
+        e->params[c][1] = P_DCT4[c][1];
+        break;
+      case ORC_DCT4X8: case ORC_DCT8X4:
+        e->mode = ORC_DQ_DCT4X8;
+        db = DB_DCT4X8[c]; nb = 4; ne = 2;
+        e->params[c][0] = P_DCT4X8[c];
+        break;
+      case ORC_DCT8: e->mode = ORC_DQ_DCT; db = DB_DCT8[c]; nb = 6; ne = 3; break;
+      case ORC_DCT16: e->mode = ORC_DQ_DCT; db = DB_DCT16[c]; nb = 7; ne = 3; break;
+      case ORC_DCT32: e->mode = ORC_DQ_DCT; db = DB_DCT32[c]; nb = 8; ne = 4; break;
+      case ORC_DCT16X8: case ORC_DCT8X16:
+        e->mode = ORC_DQ_DCT; db = DB_DCT16X8[c]; nb = 7; ne = 3; break;
+      case ORC_DCT32X8: case ORC_DCT8X32:
+        e->mode = ORC_DQ_DCT; db = DB_DCT32X8[c]; eb = EB_DCT32X8[c]; nb = 8; ne = 4; break;
+      default:
+        e->mode = ORC_DQ_DCT; db = DB_DCT32X16[c]; nb = 8; ne = 4; break;
+    }
+    e->num_bands = nb;
+    e->num_ecc_bands = ne;
+    for (int i = 0; i < nb; ++i) e->dist_bands[c][i] = db[i];
+    for (int i = 0; i < ne; ++i) e->ecc_bands[c][i] = eb ? eb[i] : 0.0;
+  }
+  return ORC_OK;
+}
+
+/* The encoding matrix s is decoded with.  Readings: Library stands for the
+ * default encoding of the matrix whose mode it is; Copy takes the encoding
+ * (resolved the same way) of the earlier matrix it names, which is then
+ * evaluated for the current transform type; matrices are indexed by
+ * transform type in the C.5.4 order, Copy naming a smaller index. */
+static int resolve_encoding(int s, const orc_dequant_encoding* enc, orc_dequant_encoding* out) {
+  int idx = s;
+  for (;;) {
+    const orc_dequant_encoding* e = enc ? &enc[idx] : NULL;
+    if (!e || e->mode == ORC_DQ_LIBRARY) return orc_default_encoding(idx, out);
+    if (e->mode == ORC_DQ_COPY) {
+      if (e->copy_from < 0 || e->copy_from >= idx) return ORC_E_DEQUANT;
+      idx = e->copy_from;
+      continue;
+    }
+    if (e->mode < 0 || e->mode > ORC_DQ_COPY) return ORC_E_DEQUANT;
+    *out = *e;
+    return ORC_OK;
+  }
+}
+
+/* The weights matrix of transform type s (X columns by Y rows) for channel c
+ * under the resolved encoding e (C.6.1). */
+static int encoding_weights(int s, int c, const orc_dequant_encoding* e, double* w) {
+  int32_t X, Y;
+  orc_varblock_size(s, &X, &Y);
+  const int banded = e->mode == ORC_DQ_DCT || e->mode == ORC_DQ_DCT4 || e->mode == ORC_DQ_DCT4X8;
+  /* the Identity, DCT2, DCT4, DCT4x8 and AFV modes only define 64-entry matrices */
+  if (e->mode != ORC_DQ_DCT && X * Y != 64) return ORC_E_DEQUANT;
+  if (banded && (e->num_bands < 2 || e->num_bands > 17 || e->num_ecc_bands < 1 ||
+                 e->num_ecc_bands > 8))
+    return ORC_E_DEQUANT;
+  const double* db = e->dist_bands[c];
+  const double* eb = e->ecc_bands[c];
+  const int nb = e->num_bands, ne = e->num_ecc_bands;
+  const double* pc = e->params[c];
+  if (e->mode == ORC_DQ_IDENTITY) {
+    for (int i = 0; i < 64; ++i) w[i] = pc[0];
+    w[0 * 8 + 1] = w[1 * 8 + 0] = pc[1];
+    w[1 * 8 + 1] = pc[2];
+  } else if (e->mode == ORC_DQ_DCT2) {
     /* Rectangles are half-open; "and symmetric" adds the mirror image across
      * the diagonal. */
     for (int y = 0; y < 8; ++y)
       for (int x = 0; x < 8; ++x) {
         int lo = x < y ? x : y, hi = x < y ? y : x;
         double v = 1.0;
-        if (hi == 1 && lo == 0) v = P_DCT2[c][0];
-        else if (hi == 1 && lo == 1) v = P_DCT2[c][1];
-        else if (hi >= 2 && hi < 4 && lo < 2) v = P_DCT2[c][2];
-        else if (hi >= 2 && hi < 4 && lo >= 2) v = P_DCT2[c][3];
-        else if (hi >= 4 && lo < 4) v = P_DCT2[c][4];
-        else if (hi >= 4 && lo >= 4) v = P_DCT2[c][5];
+        if (hi == 1 && lo == 0) v = pc[0];
+        else if (hi == 1 && lo == 1) v = pc[1];
+        else if (hi >= 2 && hi < 4 && lo < 2) v = pc[2];
+        else if (hi >= 2 && hi < 4 && lo >= 2) v = pc[3];
+        else if (hi >= 4 && lo < 4) v = pc[4];
+        else if (hi >= 4 && lo >= 4) v = pc[5];
         w[y * 8 + x] = v;
-        num[y * 8 + x] = 1.0;
       }
-  } else if (s == ORC_DCT4X8 || s == ORC_DCT8X4) {
+  } else if (e->mode == ORC_DQ_DCT4X8) {
     /* The 8-column by 4-row matrix of the band procedure, copied to (x, y)
      * from (x, y / 2); (0, 1) divided by the multiplier; transposed for
-     * DCT8x4.  Numerators as for DCT4 on the 4-point dimension (the rows of
-     * DCT4x8, the columns of DCT8x4) and I(8, pos) on the other. */
+     * DCT8x4. */
     double w84[32], w48[64];
-    dct_weights(8, 4, DB_DCT4X8[c], 4, NULL, 2, w84);
+    dct_weights(8, 4, db, nb, eb, ne, w84);
     for (int y = 0; y < 8; ++y)
       for (int x = 0; x < 8; ++x) w48[y * 8 + x] = w84[(y / 2) * 8 + x];
-    w48[1 * 8 + 0] /= P_DCT4X8[c];
+    w48[1 * 8 + 0] /= pc[0];
     for (int y = 0; y < 8; ++y)
-      for (int x = 0; x < 8; ++x) {
-        if (s == ORC_DCT4X8) {
-          w[y * 8 + x] = w48[y * 8 + x];
-          num[y * 8 + x] = orc_scale_I(8, x) * orc_scale_I(4, y / 2) / 64.0;
-        } else {
-          w[y * 8 + x] = w48[x * 8 + y];
-          num[y * 8 + x] = orc_scale_I(4, x / 2) * orc_scale_I(8, y) / 64.0;
-        }
-      }
-  } else if (s == ORC_AFV) {
+      for (int x = 0; x < 8; ++x) w[y * 8 + x] = s == ORC_DCT8X4 ? w48[x * 8 + y] : w48[y * 8 + x];
+  } else if (e->mode == ORC_DQ_AFV) {
     /* Band values: bands[0] = afv_weights[4], bands[i] = bands[i - 1] *
      * factor(afv_weights[i + 4]) (reading: the printed factor reads index
      * i + 1 while its test reads i + 4; the band parameters are 5..7).  Each
      * value fills a 2 x 2 cell group (x, y) -> (2x .. 2x+1, 2y .. 2y+1). */
+    const double* aw = e->afv_weights[c];
     double bands[4];
-    bands[0] = AFV_W[c][4];
-    for (int i = 1; i < 4; ++i) bands[i] = bands[i - 1] * band_factor(AFV_W[c][i + 4]);
+    bands[0] = aw[4];
+    for (int i = 1; i < 4; ++i) bands[i] = bands[i - 1] * band_factor(aw[i + 4]);
     const double lo = 0.8517778890324296, hi = 12.1198851366699204;
     double w4[16];
-    w4[0] = AFV_W[c][0];
-    w4[1 * 4 + 0] = AFV_W[c][1]; /* set_weight(0, 1): x = 0, y = 1 */
-    w4[0 * 4 + 1] = AFV_W[c][2]; /* set_weight(1, 0) */
-    w4[1 * 4 + 1] = AFV_W[c][3];
+    w4[0] = aw[0];
+    w4[1 * 4 + 0] = aw[1]; /* set_weight(0, 1): x = 0, y = 1 */
+    w4[0 * 4 + 1] = aw[2]; /* set_weight(1, 0) */
+    w4[1 * 4 + 1] = aw[3];
     for (int y = 0; y < 4; ++y)
       for (int x = 0; x < 4; ++x) {
         if (x < 2 && y < 2) continue;
         w4[y * 4 + x] = interpolate(AFV_FREQS[y * 4 + x] - lo, hi, bands, 4);
       }
     for (int y = 0; y < 8; ++y)
-      for (int x = 0; x < 8; ++x) {
-        w[y * 8 + x] = w4[(y / 2) * 4 + x / 2];
-        num[y * 8 + x] = 1.0;
-      }
-    w[0 * 8 + 1] *= AFV_P[c][0];
-    w[1 * 8 + 0] *= AFV_P[c][0];
-    w[1 * 8 + 1] *= AFV_P[c][1];
-  } else if (s == ORC_DCT4) {
+      for (int x = 0; x < 8; ++x) w[y * 8 + x] = w4[(y / 2) * 4 + x / 2];
+    w[0 * 8 + 1] *= pc[0];
+    w[1 * 8 + 0] *= pc[0];
+    w[1 * 8 + 1] *= pc[1];
+  } else if (e->mode == ORC_DQ_DCT4) {
     double w4[16];
-    dct_weights(4, 4, DB_DCT4[c], 4, NULL, 2, w4);
+    dct_weights(4, 4, db, nb, eb, ne, w4);
     for (int y = 0; y < 8; ++y)
       for (int x = 0; x < 8; ++x) w[y * 8 + x] = w4[(y / 2) * 4 + x / 2];
-    w[0 * 8 + 1] /= P_DCT4[c][0];
-    w[1 * 8 + 0] /= P_DCT4[c][0];
-    w[1 * 8 + 1] /= P_DCT4[c][1];
-    /* Numerators of a 4-point dimension use I(4, pos / 2); the division is by
-     * the matrix size X * Y = 64. */
-    for (int y = 0; y < 8; ++y)
-      for (int x = 0; x < 8; ++x)
-        num[y * 8 + x] = orc_scale_I(4, x / 2) * orc_scale_I(4, y / 2) / 64.0;
+    w[0 * 8 + 1] /= pc[0];
+    w[1 * 8 + 0] /= pc[0];
+    w[1 * 8 + 1] /= pc[1];
   } else {
-    const double* db;
-    const double* eb = NULL;
-    int nb, ne;
-    switch (s) {
-      case ORC_DCT8: db = DB_DCT8[c]; nb = 6; ne = 3; break;
-      case ORC_DCT16: db = DB_DCT16[c]; nb = 7; ne = 3; break;
-      case ORC_DCT32: db = DB_DCT32[c]; nb = 8; ne = 4; break;
-      case ORC_DCT16X8: case ORC_DCT8X16: db = DB_DCT16X8[c]; nb = 7; ne = 3; break;
-      case ORC_DCT32X8: case ORC_DCT8X32:
-        db = DB_DCT32X8[c]; eb = EB_DCT32X8[c]; nb = 8; ne = 4; break;
-      default: db = DB_DCT32X16[c]; nb = 8; ne = 4; break;
-    }
     dct_weights(X, Y, db, nb, eb, ne, w);
-    /* numerators(x, y) = I(X, x) * I(Y, y) / (X * Y). */
-    for (int y = 0; y < Y; ++y)
-      for (int x = 0; x < X; ++x)
-        num[y * X + x] = orc_scale_I(X, x) * orc_scale_I(Y, y) / (double)(X * Y);
   }
-  for (int i = 0; i < X * Y; ++i) {
+  return ORC_OK;
+}
+
+/* The numerators of transform type s (C.6.1), [Y][X]: 1 for AFV, DCT2 and
+ * Identity; otherwise I(N_x, f_x) I(N_y, f_y) / (X Y), where on a dimension
+ * of 4-point transforms (both of DCT4, the rows of DCT4x8, the columns of
+ * DCT8x4) N = 4 and f = pos / 2, else N = the dimension and f = pos
+ * (reading of the printed index expression, which does not distinguish X
+ * from Y or the 4-point case). */
+static void numerators(int s, double* num) {
+  int32_t X, Y;
+  orc_varblock_size(s, &X, &Y);
+  for (int32_t y = 0; y < Y; ++y)
+    for (int32_t x = 0; x < X; ++x) {
+      double v;
+      if (s == ORC_AFV || s == ORC_DCT2 || s == ORC_IDENTITY) v = 1.0;
+      else if (s == ORC_DCT4) v = orc_scale_I(4, x / 2) * orc_scale_I(4, y / 2) / 64.0;
+      else if (s == ORC_DCT4X8) v = orc_scale_I(8, x) * orc_scale_I(4, y / 2) / 64.0;
+      else if (s == ORC_DCT8X4) v = orc_scale_I(4, x / 2) * orc_scale_I(8, y) / 64.0;
+      else v = orc_scale_I(X, x) * orc_scale_I(Y, y) / (double)(X * Y);
+      num[y * X + x] = v;
+    }
+}
+
+int orc_dequant_matrix_enc(int s, int c, const orc_dequant_encoding* enc, double* out) {
+  int32_t bx, by;
+  if (!supported(s) || !orc_varblock_size(s, &bx, &by)) return ORC_E_STRATEGY;
+  if (c < 0 || c > 2) return ORC_E_PARAM;
+  orc_dequant_encoding e;
+  int st = resolve_encoding(s, enc, &e);
+  if (st) return st;
+  double w[32 * 32], num[32 * 32];
+  st = encoding_weights(s, c, &e, w);
+  if (st) return st;
+  numerators(s, num);
+  for (int i = 0; i < bx * by; ++i) {
     double v = num[i] / w[i];
+    /* entry (0, 0) is never a multiplier (the DC comes from the DC image) */
     if (i != 0 && !(v > 0.0 && isfinite(v))) return ORC_E_DEQUANT;
     out[i] = v;
   }
   return ORC_OK;
+}
+
+int orc_dequant_matrix(int s, int c, double* out) {
+  return orc_dequant_matrix_enc(s, c, NULL, out);
 }
 
 /* ======================================================================= */
@@ -979,17 +1068,40 @@ static int check_params(const orc_params* p) {
   if (!(p->epf_weight_min <= 1.0)) return ORC_E_PARAM;
   for (int c = 0; c < 3; ++c)
     if (p->extra_levels[c] < 0 || p->extra_levels[c] > 3) return ORC_E_PARAM;
+  /* every real-valued field must be finite (a NaN would pass the range tests
+   * above and then reach integer conversions) */
+  const double* fin[] = {p->dc_mul, &p->kx_dc, &p->kb_dc, p->gab_w1, p->gab_w2,
+                         &p->epf_weight_min, p->epf_scale, p->epf_sharp_lut, &p->epf_range_max,
+                         &p->epf_range_mul, &p->epf_quant_mul, p->opsin_inv, p->opsin_bias,
+                         &p->qco_interval_mul, p->noise_lut, p->dot_colour_quant};
+  const int nfin[] = {3, 1, 1, 3, 3, 1, 3, 8, 1, 1, 1, 9, 3, 1, 16, 3};
+  for (size_t k = 0; k < sizeof(nfin) / sizeof(nfin[0]); ++k)
+    for (int i = 0; i < nfin[k]; ++i)
+      if (!isfinite(fin[k][i])) return ORC_E_PARAM;
+  /* the DcQuantField is a positive dequantization range */
+  if (p->dc_quant_field) {
+    const size_t n = 3 * (size_t)((p->xsize + 7) / 8) * ((p->ysize + 7) / 8);
+    for (size_t i = 0; i < n; ++i)
+      if (!(p->dc_quant_field[i] > 0.0f && isfinite(p->dc_quant_field[i]))) return ORC_E_PARAM;
+  }
   return ORC_OK;
+}
+
+/* The dequantization range (DcQuantField of C.5.2) of DC sample (x, y) of
+ * channel c. */
+static double dc_range(const orc_params* p, int c, int32_t x, int32_t y) {
+  const int32_t Wb = (p->xsize + 7) / 8, Hb = (p->ysize + 7) / 8;
+  if (p->dc_quant_field) return p->dc_quant_field[((size_t)c * Hb + y) * Wb + x];
+  return p->dc_mul[c] / (double)(1 << p->extra_levels[c]);
 }
 
 /* F.2 adaptive DC smoothing of the dequantized DC image, per channel, in
  * place: every sample away from the first and last row and column becomes the
  * 3x3 weighted average of the unsmoothed samples (centre 0.05226273532324128,
  * edge neighbours 0.20345139757231578, diagonal ones 0.0334829185968739) when
- * that average lies within 0.5 dcq of the sample, else keeps its value.
- * Readings: dcq is the channel's DC multiplier divided by 2^extra_levels (the
- * DcQuantField of C.5.2 for a zero decoded delta, and the multiplier itself
- * when extra_levels is 0); the smoothing precedes the DC chroma from luma. */
+ * that average lies within 0.5 dcq of the sample, else keeps its value;
+ * dcq is the sample's DcQuantField (C.5.2).  Reading: the smoothing precedes
+ * the DC chroma from luma. */
 void orc_dc_smooth(const orc_params* p, int32_t Wb, int32_t Hb, double* dcq) {
   const double wc = 0.05226273532324128, we = 0.20345139757231578, wd = 0.0334829185968739;
   double* src = (double*)malloc(sizeof(double) * Wb * Hb);
@@ -997,9 +1109,9 @@ void orc_dc_smooth(const orc_params* p, int32_t Wb, int32_t Hb, double* dcq) {
   for (int c = 0; c < 3; ++c) {
     double* d = dcq + (size_t)c * Wb * Hb;
     memcpy(src, d, sizeof(double) * Wb * Hb);
-    const double q = p->dc_mul[c] / (double)(1 << p->extra_levels[c]);
     for (int32_t y = 1; y + 1 < Hb; ++y)
       for (int32_t x = 1; x + 1 < Wb; ++x) {
+        const double q = dc_range(p, c, x, y);
         const double* r0 = src + (size_t)(y - 1) * Wb + x;
         const double* r1 = src + (size_t)y * Wb + x;
         const double* r2 = src + (size_t)(y + 1) * Wb + x;
@@ -1023,9 +1135,10 @@ void orc_dc_smooth(const orc_params* p, int32_t Wb, int32_t Hb, double* dcq) {
  * (0.12 centre, 0.2 edge, 0.02 diagonal neighbours) of the unsmoothed cells
  * replaces the cell when within 1.7 dcq of it.  The smoothed cells are
  * stored in out [3][2 Hb][2 Wb] (cell (2 bx + i, 2 by + j) of block (bx, by)).
- * Readings: the DC samples are the ones the LLF is computed from (after
- * F.2 smoothing and the DC chroma from luma); dcq is the DC multiplier over
- * 2^extra_levels, as in F.2; "xsize x ysize" of a group counts blocks. */
+ * dcq is the channel's DC multiplier (C.4.1 with the C.4.2 fields; not the
+ * per-sample DcQuantField that F.2 uses).  Readings: the DC samples are the
+ * ones the LLF is computed from (after F.2 smoothing and the DC chroma from
+ * luma); "xsize x ysize" of a group counts blocks. */
 void orc_ac_prediction_image(const orc_params* p, int32_t Wb, int32_t Hb,
                              const uint8_t* strategy, const double* dcq, double* out,
                              double* margin) {
@@ -1035,7 +1148,7 @@ void orc_ac_prediction_image(const orc_params* p, int32_t Wb, int32_t Hb,
   if (!img || !sm) { free(img); free(sm); return; }
   for (int c = 0; c < 3; ++c) {
     const double* d = dcq + (size_t)c * Wb * Hb;
-    const double q = p->dc_mul[c] / (double)(1 << p->extra_levels[c]);
+    const double q = p->dc_mul[c];
     for (int32_t gy0 = 0; gy0 < Hb; gy0 += 32)
       for (int32_t gx0 = 0; gx0 < Wb; gx0 += 32) {
         const int32_t gw = Wb - gx0 < 32 ? Wb - gx0 : 32, gh = Hb - gy0 < 32 ? Hb - gy0 : 32;
@@ -1104,7 +1217,7 @@ int orc_reconstruct(const orc_params* p, const int32_t* const ac[3], const int32
   if (!dq) return ORC_E_SIZE;
   for (int s = 0; s < 15; ++s)
     for (int c = 0; c < 3; ++c) {
-      st = orc_dequant_matrix(s, c, dq[s][c]);
+      st = orc_dequant_matrix_enc(s, c, p->dq_enc, dq[s][c]);
       if (st) { free(dq); return st; }
     }
 
@@ -1430,8 +1543,7 @@ static double forward_gain(int s, int32_t bx, int32_t by) {
  * orig.  Readings:
  *   - the step of a coefficient outside the LLF corner is its dequantization
  *     matrix entry times AcMul (the factor F.3 multiplies a quantized value
- *     by), of a DC sample the DC multiplier over 2^extra_levels (the
- *     DcQuantField of C.5.2 for a zero decoded delta);
+ *     by), of a DC sample its DcQuantField (C.5.2);
  *   - samples of a varblock outside the frame were never filtered: their
  *     residual is 0, and only samples inside the frame are written;
  *   - the clamp acts on each channel's own coefficients (chroma from luma
@@ -1447,7 +1559,7 @@ int orc_qco(const orc_params* p, const uint8_t* strategy, const uint8_t* qf_minu
   varblock* list = (varblock*)malloc(sizeof(varblock) * Wb * Hb);
   if (!dq || !list) { free(dq); free(list); return ORC_E_SIZE; }
   for (int s = 0; s < 15 && !st; ++s)
-    for (int c = 0; c < 3 && !st; ++c) st = orc_dequant_matrix(s, c, dq[s][c]);
+    for (int c = 0; c < 3 && !st; ++c) st = orc_dequant_matrix_enc(s, c, p->dq_enc, dq[s][c]);
   int32_t nvb = 0;
   if (!st) st = scan_varblocks(Wb, Hb, strategy, list, &nvb, NULL);
   if (st) { free(dq); free(list); return st; }
@@ -1488,8 +1600,10 @@ int orc_qco(const orc_params* p, const uint8_t* strategy, const uint8_t* qf_minu
           }
         }
       orc_dc_from_llf(vb.s, L, D);
-      const double tq = m * p->dc_mul[c] / (double)(1 << p->extra_levels[c]);
-      for (int32_t i = 0; i < cx * cy; ++i) D[i] = fmin(fmax(D[i], -tq), tq);
+      for (int32_t i = 0; i < cx * cy; ++i) {
+        const double tq = m * dc_range(p, c, vb.bx0 + i % cx, vb.by0 + i / cx);
+        D[i] = fmin(fmax(D[i], -tq), tq);
+      }
       orc_llf_from_dc(vb.s, D, L);
       for (int32_t y = 0; y < cy; ++y)
         for (int32_t x = 0; x < cx; ++x) K[y * bx + x] = L[y * cx + x];

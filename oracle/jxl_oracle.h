@@ -53,6 +53,25 @@ enum {
   ORC_DCT8X4 = 13, ORC_AFV = 14
 };
 
+/* Encoding of one dequantization matrix (C.6.1), already read from the
+ * stream: the encoding mode and the parameters that mode reads, per channel
+ * X, Y, B.  Parameters a mode does not read are ignored. */
+enum {
+  ORC_DQ_LIBRARY = 0, ORC_DQ_IDENTITY = 1, ORC_DQ_DCT2 = 2, ORC_DQ_DCT4 = 3,
+  ORC_DQ_DCT4X8 = 4, ORC_DQ_AFV = 5, ORC_DQ_DCT = 6, ORC_DQ_COPY = 7
+};
+typedef struct {
+  int32_t mode;                 /* ORC_DQ_* */
+  int32_t copy_from;            /* Copy: index of an earlier matrix */
+  int32_t num_bands;            /* DCT, DCT4, DCT4x8: 2..17 distance bands */
+  int32_t num_ecc_bands;        /* DCT, DCT4, DCT4x8: 1..8 eccentricity bands */
+  double  dist_bands[3][17];    /* db */
+  double  ecc_bands[3][8];      /* eb */
+  double  params[3][6];         /* Identity 3, DCT2 6, DCT4 2, DCT4x8 1
+                                   (dct4x8multipliers), AFV 2 (dct4multipliers) */
+  double  afv_weights[3][8];    /* AFV */
+} orc_dequant_encoding;
+
 /* Frame parameters decoded from the headers (C.2, C.4, C.10, A.4.5, L.2). */
 typedef struct {
   int32_t xsize, ysize;
@@ -79,6 +98,14 @@ typedef struct {
   int32_t noise;               /* kNoise (K.5); 0 = skipped */
   double  noise_lut[16];       /* C.4.8 LUT, each u(10) / 1024 */
   double  dot_colour_quant[3]; /* kColourQuant of K.2.1 (not given by the draft) */
+  /* C.6.1 encodings of the 15 dequantization matrices, indexed by transform
+   * type (C.5.4 numbering); NULL: all have their C.6.1.1 default encoding. */
+  const orc_dequant_encoding* dq_enc;
+  /* C.5.2 DcQuantField, float [3][Hb][Wb]: the dequantization range of each
+   * DC sample (F.2 smoothing, J.3 LLF clamp); NULL: dc_mul[c] /
+   * 2^extra_levels[c] everywhere (the field of a DC plane whose decoded
+   * deltas are all 0; with extra_levels 0, the field whatever the deltas). */
+  const float* dc_quant_field;
 } orc_params;
 
 /* Fills the defaults the draft gives for every field (C.4, C.10, L.2, A.4.5). */
@@ -116,6 +143,12 @@ int orc_llf2x2_from_dc2x2(int strategy, const double* cells, double* coeffs);
 /* ---- dequantization (C.6.1, F.3) --------------------------------------- */
 /* Default dequantization matrix of a transform type and channel, [by][bx]. */
 int orc_dequant_matrix(int strategy, int c, double* out);
+/* The matrix of a transform type and channel under the encodings enc[15]
+ * (NULL: defaults), [by][bx]; ORC_E_DEQUANT when the encoding is not valid
+ * for the type or an entry is not positive and finite. */
+int orc_dequant_matrix_enc(int strategy, int c, const orc_dequant_encoding* enc, double* out);
+/* The C.6.1.1 default encoding of a transform type (mode and parameters). */
+int orc_default_encoding(int strategy, orc_dequant_encoding* out);
 
 /* ---- reconstruction (F, G, I) ------------------------------------------ */
 /* Quantized DC/AC planes and side maps -> XYB samples, cropped to xsize x ysize.

@@ -41,7 +41,45 @@ class OrcParams(C.Structure):
         ("noise", C.c_int32),
         ("noise_lut", C.c_double * 16),
         ("dot_colour_quant", C.c_double * 3),
+        ("dq_enc", C.c_void_p),
+        ("dc_quant_field", C.c_void_p),
     ]
+
+
+class OrcDequantEncoding(C.Structure):
+    _fields_ = [
+        ("mode", C.c_int32), ("copy_from", C.c_int32),
+        ("num_bands", C.c_int32), ("num_ecc_bands", C.c_int32),
+        ("dist_bands", (C.c_double * 17) * 3),
+        ("ecc_bands", (C.c_double * 8) * 3),
+        ("params", (C.c_double * 6) * 3),
+        ("afv_weights", (C.c_double * 8) * 3),
+    ]
+
+
+def _encoding_struct(e):
+    """OrcDequantEncoding from a dict (mode, copy_from, num_bands,
+    num_ecc_bands, dist_bands [3][<=17], ecc_bands [3][<=8], params [3][<=6],
+    afv_weights [3][8]); absent keys are 0."""
+    out = OrcDequantEncoding()
+    for k in ("mode", "copy_from", "num_bands", "num_ecc_bands"):
+        setattr(out, k, int(e.get(k, 0)))
+    for k in ("dist_bands", "ecc_bands", "params", "afv_weights"):
+        if k in e:
+            arr = getattr(out, k)
+            for c, row in enumerate(e[k]):
+                for i, v in enumerate(row):
+                    arr[c][i] = float(v)
+    return out
+
+
+def _encoding_dict(st):
+    return {"mode": st.mode, "copy_from": st.copy_from, "num_bands": st.num_bands,
+            "num_ecc_bands": st.num_ecc_bands,
+            "dist_bands": [list(st.dist_bands[c])[:st.num_bands] for c in range(3)],
+            "ecc_bands": [list(st.ecc_bands[c])[:st.num_ecc_bands] for c in range(3)],
+            "params": [list(st.params[c]) for c in range(3)],
+            "afv_weights": [list(st.afv_weights[c]) for c in range(3)]}
 
 
 _i32p = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
@@ -76,6 +114,8 @@ def lib():
         L.orc_ac_prediction_image.argtypes = [P, C.c_int32, C.c_int32, _u8p, _f64p, _f64p,
                                               C.c_void_p]
         L.orc_dequant_matrix.argtypes = [C.c_int, C.c_int, _f64p]
+        L.orc_dequant_matrix_enc.argtypes = [C.c_int, C.c_int, C.c_void_p, _f64p]
+        L.orc_default_encoding.argtypes = [C.c_int, C.POINTER(OrcDequantEncoding)]
         L.orc_afv_basis.argtypes = [_f64p]
         L.orc_dc_smooth.argtypes = [P, C.c_int32, C.c_int32, _f64p]
         ptr3 = C.c_void_p * 3
@@ -142,10 +182,19 @@ def varblock_size(s):
     return bx.value, by.value
 
 
-def params(xsize, ysize, **overrides):
-    """Oracle parameter struct: the draft's defaults, then `overrides`."""
+def params(xsize, ysize, dq_enc=None, **overrides):
+    """Oracle parameter struct: the draft's defaults, then `overrides`.
+    dq_enc: None (the C.6.1.1 defaults) or 15 encoding dicts (see
+    _encoding_struct), indexed by transform type."""
     p = OrcParams()
     lib().orc_params_default(C.byref(p), int(xsize), int(ysize))
+    p._keep = {}
+    if dq_enc is not None:
+        if len(dq_enc) != 15:
+            raise ValueError("dq_enc needs 15 encodings")
+        arr = (OrcDequantEncoding * 15)(*[_encoding_struct(e) for e in dq_enc])
+        p._keep["dq_enc"] = arr
+        p.dq_enc = C.cast(arr, C.c_void_p)
     for k, v in overrides.items():
         cur = getattr(p, k)
         if isinstance(cur, C.Array):
@@ -259,10 +308,12 @@ def ac_prediction_image(p, strategy, dcq, want_margin=False):
     return (out, margin) if want_margin else out
 
 
-def dc_smooth(p, dcq):
-    """F.2 adaptive DC smoothing of a dequantized DC image (3, Hb, Wb)."""
+def dc_smooth(p, dcq, field=None):
+    """F.2 adaptive DC smoothing of a dequantized DC image (3, Hb, Wb);
+    field: its DcQuantField (3, Hb, Wb), or None."""
     d = np.array(dcq, dtype=np.float64, order="C", copy=True)
-    lib().orc_dc_smooth(C.byref(p), d.shape[2], d.shape[1], d)
+    with _Field(p, {"dc_quant": field} if field is not None else None):
+        lib().orc_dc_smooth(C.byref(p), d.shape[2], d.shape[1], d)
     return d
 
 
@@ -272,11 +323,46 @@ def afv_basis():
     return out.reshape(16, 16)
 
 
-def dequant_matrix(s, c):
+def dequant_matrix(s, c, dq_enc=None):
+    """Dequantization matrix (by, bx) of type s and channel c under the
+    encodings dq_enc (None: the C.6.1.1 defaults)."""
     bx, by = varblock_size(s)
     out = np.zeros(bx * by)
-    _check(lib().orc_dequant_matrix(s, c, out))
+    if dq_enc is None:
+        _check(lib().orc_dequant_matrix(s, c, out))
+    else:
+        arr = (OrcDequantEncoding * 15)(*[_encoding_struct(e) for e in dq_enc])
+        _check(lib().orc_dequant_matrix_enc(s, c, C.cast(arr, C.c_void_p), out))
     return out.reshape(by, bx)
+
+
+def default_encoding(s):
+    """The C.6.1.1 default encoding of type s, as a dict."""
+    st = OrcDequantEncoding()
+    _check(lib().orc_default_encoding(s, C.byref(st)))
+    return _encoding_dict(st)
+
+
+class _Field:
+    """Points p.dc_quant_field at frame["dc_quant"] (C.5.2 DcQuantField,
+    float (3, Hb, Wb)) for the duration of a call, if the frame has one."""
+
+    def __init__(self, p, frame):
+        self.p, self.frame = p, frame
+
+    def __enter__(self):
+        f = self.frame.get("dc_quant") if self.frame is not None else None
+        self.old = self.p.dc_quant_field
+        if f is not None:
+            self.arr = np.ascontiguousarray(f, np.float32)
+            Hb, Wb = (self.p.ysize + 7) // 8, (self.p.xsize + 7) // 8
+            if self.arr.shape != (3, Hb, Wb):
+                raise ValueError("dc_quant must be (3, Hb, Wb)")
+            self.p.dc_quant_field = self.arr.ctypes.data
+        return self
+
+    def __exit__(self, *a):
+        self.p.dc_quant_field = self.old
 
 
 def _planes(arrs, dtype):
@@ -292,11 +378,12 @@ def reconstruct(p, frame):
     ka, pa = _planes(frame["ac"], np.int32)
     kd, pd = _planes(frame["dc"], np.int32)
     out = np.zeros((3, p.ysize, p.xsize))
-    _check(lib().orc_reconstruct(
-        C.byref(p), pa, pd, np.ascontiguousarray(frame["strategy"], np.uint8),
-        np.ascontiguousarray(frame["qf"], np.uint8),
-        np.ascontiguousarray(frame["cfl_kx"], np.float32),
-        np.ascontiguousarray(frame["cfl_kb"], np.float32), out))
+    with _Field(p, frame):
+        _check(lib().orc_reconstruct(
+            C.byref(p), pa, pd, np.ascontiguousarray(frame["strategy"], np.uint8),
+            np.ascontiguousarray(frame["qf"], np.uint8),
+            np.ascontiguousarray(frame["cfl_kx"], np.float32),
+            np.ascontiguousarray(frame["cfl_kb"], np.float32), out))
     return out
 
 
@@ -334,9 +421,10 @@ def qco(p, frame, orig, filt):
     orig = np.ascontiguousarray(orig, dtype=np.float64)
     filt = np.ascontiguousarray(filt, dtype=np.float64)
     out = np.zeros_like(filt)
-    _check(lib().orc_qco(
-        C.byref(p), np.ascontiguousarray(frame["strategy"], np.uint8),
-        np.ascontiguousarray(frame["qf"], np.uint8), orig, filt, out))
+    with _Field(p, frame):
+        _check(lib().orc_qco(
+            C.byref(p), np.ascontiguousarray(frame["strategy"], np.uint8),
+            np.ascontiguousarray(frame["qf"], np.uint8), orig, filt, out))
     return out
 
 
@@ -509,6 +597,12 @@ def decode(p, frame):
     so = np.ascontiguousarray(so, np.int32) if ns else None
     sp = np.ascontiguousarray(frame["spline_points"], np.int32) if ns else None
     sd = np.ascontiguousarray(frame["spline_dct"], np.float32) if ns else None
+    with _Field(p, frame):
+        _decode_features(p, frame, pa, pd, pl, n, sm, dt, nd, so, ns, sp, sd, out)
+    return out
+
+
+def _decode_features(p, frame, pa, pd, pl, n, sm, dt, nd, so, ns, sp, sd, out):
     _check(lib().orc_decode_features(
         C.byref(p), pa, pd, np.ascontiguousarray(frame["strategy"], np.uint8),
         np.ascontiguousarray(frame["qf"], np.uint8),
@@ -518,7 +612,6 @@ def decode(p, frame):
         pl.ctypes.data if n else None, n, sm.ctypes.data if n else None,
         dt.ctypes.data if nd else None, nd, so.ctypes.data if ns else None, ns,
         sp.ctypes.data if ns else None, sd.ctypes.data if ns else None, out))
-    return out
 
 
 def decode_stages(p, frame):

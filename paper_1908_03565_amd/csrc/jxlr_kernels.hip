@@ -451,21 +451,87 @@ __device__ inline void split2(float v0, float v1, uint32_t& hi, uint32_t& lo) {
   lo = __builtin_bit_cast(uint32_t, __builtin_convertvector(r, bf16x2));
 }
 
+// The binary32 transform of the varblocks' LLF corners for one lane's
+// accumulators of the row product (acc[q] = sample (row j, column i) of the
+// region, i = 8 (q / 4) + 4 kh + q mod 4), written as their starting values.
+// Q[t]: the lane's row j of the corners after the column transform, t =
+// (varblock column) * cx + (LLF column v), cx = 2^MR LLF columns per
+// varblock of 8 cx samples; c1[n] = cos(pi (2 n + 1) / (16 cx)), and
+// cos(v phi) for v = 2, 3 follows from it (2 c^2 - 1, (4 c^2 - 3) c).
+template <int MR>
+__device__ inline void llf_row_init(f32x16& acc, const float (&Q)[4],
+                                    const float* __restrict__ c1, int kh) {
+  constexpr int cx = 1 << MR;
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int base = ((q >> 2) >> MR) << MR;  // first t of the varblock holding column i
+    float a = Q[base];
+    if constexpr (cx > 1) {
+      const int i = 8 * (q >> 2) + 4 * kh + (q & 3);
+      const float c = c1[i & (8 * cx - 1)];
+      a = fmaf(Q[base + 1], c, a);
+      if constexpr (cx > 2) {
+        const float c2 = c * c;
+        a = fmaf(Q[base + 2], fmaf(2.0f, c2, -1.0f), a);
+        a = fmaf(Q[base + 3], fmaf(4.0f, c2, -3.0f) * c, a);
+      }
+    }
+    acc[q] = a;
+  }
+}
+
 // One wave transforms the 32x32 block of cf starting at column col0, in
-// place.  Acol / Arow: the DeviceTables::mfma_a operands [part][step][lane][8]
-// of the column and row matrices.  Only the calling wave touches the block,
-// and the LDS accesses of one wave complete in issue order, so the reads of
-// the second product see the first product's stores without a workgroup
-// barrier; the caller synchronizes before other waves read the block.
-__device__ inline void mfma_region(float (*cf)[kRecLd], int col0, const uint16_t* __restrict__ Acol,
-                                   const uint16_t* __restrict__ Arow, int lane) {
+// place.  m: the operand selector (column matrix | row matrix << 2, each
+// 0, 1, 2 for 8, 16, 32-sample varblock sides); Acol / Arow: the
+// DeviceTables::mfma_a operands [part][step][lane][8] of the column and row
+// matrices.  Only the high-frequency coefficients go through the split
+// products: each varblock's LLF corner (its top cy x cx coefficients, which
+// carry the DC and the largest values) is zeroed in the column product's
+// operand and transformed in binary32 on the side, the column step before
+// the products and the row step as the row product's starting accumulators
+// (the transform is linear, so the two parts sum to the whole).  Only the
+// calling wave touches the block, and the LDS accesses of one wave complete
+// in issue order, so the reads of the second product see the first
+// product's stores without a workgroup barrier; the caller synchronizes
+// before other waves read the block.
+__device__ inline void mfma_region(float (*cf)[kRecLd], int col0, int m,
+                                   const DeviceTables* __restrict__ T, int lane) {
   const int j = lane & 31, kh = lane >> 5;
+  const int mc = m & 3, mr = m >> 2;
+  const int nc = 8 << mc, nr = 8 << mr, cy = 1 << mc, cx = 1 << mr;
+  // LLF corners, column step, for the row j this lane takes in the row
+  // product: Q[t] = sum over u < cy of cos(pi (2 (j mod nc) + 1) u / (2 nc))
+  // times coefficient (row vy0 + u, column of t), t = vx * cx + v.
+  float Q[4];
+  {
+    const float4 cc = *reinterpret_cast<const float4*>(T->llf_cos[mc][j & (nc - 1)]);
+    const float cu[4] = {cc.x, cc.y, cc.z, cc.w};
+    const int vy0 = j & ~(nc - 1);
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int col = col0 + (t >> mr) * nr + (t & (cx - 1));
+      float a = 0.0f;
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (u < cy) a = fmaf(cu[u], cf[vy0 + u][col], a);
+      Q[t] = a;
+    }
+  }
+  const bool llf_col = (j & (nr - 1)) < cx;  // pass 0: column j holds LLF entries
 #pragma unroll
   for (int pass = 0; pass < 2; ++pass) {
-    const uint16_t* A = pass == 0 ? Acol : Arow;
+    const uint16_t* A = &T->mfma_a[pass == 0 ? mc : mr][0][0][0][0];
     f32x16 acc;
+    if (pass == 0) {
 #pragma unroll
-    for (int q = 0; q < 16; ++q) acc[q] = 0.0f;
+      for (int q = 0; q < 16; ++q) acc[q] = 0.0f;
+    } else {
+      // the row product accumulates onto the LLF corners' samples
+      const float* c1 = T->llf_c1[mr];
+      if (mr == 0) llf_row_init<0>(acc, Q, c1, kh);
+      else if (mr == 1) llf_row_init<1>(acc, Q, c1, kh);
+      else llf_row_init<2>(acc, Q, c1, kh);
+    }
 #pragma unroll
     for (int step = 0; step < 2; ++step) {
       const bf16x8 ah = *reinterpret_cast<const bf16x8*>(A + ((0 * 2 + step) * 64 + lane) * 8);
@@ -474,9 +540,19 @@ __device__ inline void mfma_region(float (*cf)[kRecLd], int col0, const uint16_t
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const int k = 16 * step + 8 * kh + 2 * e;
-        // pass 0: B = K[k][j]; pass 1: B = Y^T[k][j] = Y[j][k]
-        const float v0 = pass == 0 ? cf[k][col0 + j] : cf[j][col0 + k];
-        const float v1 = pass == 0 ? cf[k + 1][col0 + j] : cf[j][col0 + k + 1];
+        // pass 0: B = K[k][j] without the LLF corners; pass 1: B = Y^T[k][j] = Y[j][k]
+        float v0, v1;
+        if (pass == 0) {
+          v0 = cf[k][col0 + j];
+          v1 = cf[k + 1][col0 + j];
+          if (llf_col) {
+            if ((k & (nc - 1)) < cy) v0 = 0.0f;
+            if (((k + 1) & (nc - 1)) < cy) v1 = 0.0f;
+          }
+        } else {
+          v0 = cf[j][col0 + k];
+          v1 = cf[j][col0 + k + 1];
+        }
         uint32_t h, l;
         split2(v0, v1, h, l);
         bh[e] = h;
@@ -778,8 +854,7 @@ __device__ __attribute__((always_inline)) inline void recon_tile(const ReconArgs
     for (int r = 0; r < 2; ++r) {
       const int m = s_mma[r];
       if (m < 0) continue;
-      mfma_region(coef[wave], 32 * r, &T->mfma_a[m & 3][0][0][0][0], &T->mfma_a[m >> 2][0][0][0][0],
-                  lane);
+      mfma_region(coef[wave], 32 * r, m, T, lane);
     }
     __syncthreads();
   }

@@ -215,13 +215,13 @@ double interp(double pos, double span, const std::vector<double>& pts) {
   return pts[i] * std::pow(pts[i + 1] / pts[i], sp - fl);
 }
 
-// DCT-mode weight matrix for X columns and Y rows, row-major.
-std::vector<double> band_weights(int X, int Y, const BandSet& dist, const BandSet* ecc, int c,
-                                 int n_ecc) {
+// DCT-mode weight matrix for X columns and Y rows, row-major, from nb
+// encoded distance bands and ne encoded eccentricity bands.
+std::vector<double> band_weights(int X, int Y, const double* db, int nb, const double* eb,
+                                 int ne) {
   // distance bands: db[0], then one multiplier per further encoded value
-  std::vector<double> dpts = cumulative(dist.v[c][0], &dist.v[c][1], dist.n - 1);
-  std::vector<double> zeros(8, 0.0);
-  std::vector<double> epts = cumulative(1.0, ecc ? ecc->v[c] : zeros.data(), n_ecc);
+  std::vector<double> dpts = cumulative(db[0], db + 1, nb - 1);
+  std::vector<double> epts = cumulative(1.0, eb, ne);
   std::vector<double> w(size_t(X) * Y);
   for (int y = 0; y < Y; ++y) {
     for (int x = 0; x < X; ++x) {
@@ -235,7 +235,85 @@ std::vector<double> band_weights(int X, int Y, const BandSet& dist, const BandSe
   return w;
 }
 
+void set_bands(DequantEncoding* e, const BandSet& dist, const BandSet* ecc, int n_ecc) {
+  e->num_bands = dist.n;
+  e->num_ecc_bands = n_ecc;
+  for (int c = 0; c < 3; ++c) {
+    for (int i = 0; i < dist.n; ++i) e->dist_bands[c][i] = dist.v[c][i];
+    for (int i = 0; i < n_ecc; ++i) e->ecc_bands[c][i] = ecc ? ecc->v[c][i] : 0.0;
+  }
+}
+
+// The encoding matrix s is built from: Library is the default of the matrix
+// it stands for, Copy follows to the earlier matrix it names (and that one's
+// encoding is evaluated for type s).  False for a Copy that does not name an
+// earlier matrix or an unknown mode.
+bool resolve(int s, const DequantEncoding* enc, DequantEncoding* out) {
+  int idx = s;
+  while (true) {
+    if (!enc || enc[idx].mode == kDqLibrary) {
+      default_encoding(idx, out);
+      return true;
+    }
+    const DequantEncoding& e = enc[idx];
+    if (e.mode == kDqCopy) {
+      if (e.copy_from < 0 || e.copy_from >= idx) return false;
+      idx = e.copy_from;
+      continue;
+    }
+    if (e.mode < kDqIdentity || e.mode > kDqDct) return false;
+    *out = e;
+    return true;
+  }
+}
+
 }  // namespace
+
+void default_encoding(int s, DequantEncoding* e) {
+  std::memset(e, 0, sizeof(*e));
+  switch (s) {
+    case 1:
+      e->mode = kDqIdentity;
+      for (int c = 0; c < 3; ++c)
+        for (int i = 0; i < 3; ++i) e->params[c][i] = kIdentityW[c][i];
+      break;
+    case 2:
+      e->mode = kDqDct2;
+      for (int c = 0; c < 3; ++c)
+        for (int i = 0; i < 6; ++i) e->params[c][i] = kDct2W[c][i];
+      break;
+    case 3:
+      e->mode = kDqDct4;
+      set_bands(e, kDist4, nullptr, 2);
+      for (int c = 0; c < 3; ++c)
+        for (int i = 0; i < 2; ++i) e->params[c][i] = kDct4Mul[c][i];
+      break;
+    case 12:
+    case 13:
+      e->mode = kDqDct4x8;
+      set_bands(e, kDist4x8, nullptr, 2);
+      for (int c = 0; c < 3; ++c) e->params[c][0] = kDct4x8Mul[c];
+      break;
+    case 14:
+      e->mode = kDqAfv;
+      for (int c = 0; c < 3; ++c) {
+        for (int i = 0; i < 8; ++i) e->afv_weights[c][i] = kAfvW[c][i];
+        for (int i = 0; i < 2; ++i) e->params[c][i] = kAfvMul[c][i];
+      }
+      break;
+    default:
+      e->mode = kDqDct;
+      switch (s) {
+        case 0: set_bands(e, kDist8, nullptr, 3); break;
+        case 4: set_bands(e, kDist16, nullptr, 3); break;
+        case 5: set_bands(e, kDist32, nullptr, 4); break;
+        case 6: case 7: set_bands(e, kDist16x8, nullptr, 3); break;
+        case 8: case 9: set_bands(e, kDist32x8, &kEcc32x8, 4); break;
+        default: set_bands(e, kDist32x16, nullptr, 4); break;
+      }
+      break;
+  }
+}
 
 int dq_offset(int s) {
   int off = 0;
@@ -243,18 +321,28 @@ int dq_offset(int s) {
   return off;
 }
 
-bool dequant_matrix_f64(int s, int c, double* out) {
+bool dequant_matrix_f64(int s, int c, double* out, const DequantEncoding* enc) {
   const int X = 8 * blocks_x(s), Y = 8 * blocks_y(s);
+  DequantEncoding e;
+  if (!resolve(s, enc, &e)) return false;
+  // the Identity, DCT2, DCT4, DCT4x8 and AFV modes define 64-entry matrices only
+  if (e.mode != kDqDct && X * Y != 64) return false;
+  if ((e.mode == kDqDct || e.mode == kDqDct4 || e.mode == kDqDct4x8) &&
+      (e.num_bands < 2 || e.num_bands > 17 || e.num_ecc_bands < 1 || e.num_ecc_bands > 8))
+    return false;
   std::vector<double> w(size_t(X) * Y, 1.0), num(size_t(X) * Y, 1.0);
   auto at = [X](std::vector<double>& m, int x, int y) -> double& { return m[size_t(y) * X + x]; };
-  switch (s) {
-    case 1: {  // Identity mode
-      for (auto& v : w) v = kIdentityW[c][0];
-      at(w, 1, 0) = at(w, 0, 1) = kIdentityW[c][1];
-      at(w, 1, 1) = kIdentityW[c][2];
+  const double* prm = e.params[c];
+  const double* db = e.dist_bands[c];
+  const double* eb = e.ecc_bands[c];
+  switch (e.mode) {
+    case kDqIdentity: {
+      for (auto& v : w) v = prm[0];
+      at(w, 1, 0) = at(w, 0, 1) = prm[1];
+      at(w, 1, 1) = prm[2];
       break;
     }
-    case 2: {  // DCT2 mode: index by the larger and smaller coordinate
+    case kDqDct2: {  // index by the larger and smaller coordinate
       for (int y = 0; y < 8; ++y)
         for (int x = 0; x < 8; ++x) {
           const int hi = std::max(x, y), lo = std::min(x, y);
@@ -262,70 +350,63 @@ bool dequant_matrix_f64(int s, int c, double* out) {
           if (hi == 1) k = lo;                 // (0,1)/(1,0) -> 0, (1,1) -> 1
           else if (hi >= 2 && hi < 4) k = lo < 2 ? 2 : 3;
           else if (hi >= 4) k = lo < 4 ? 4 : 5;
-          if (k >= 0) at(w, x, y) = kDct2W[c][k];
+          if (k >= 0) at(w, x, y) = prm[k];
         }
       break;
     }
-    case 12:
-    case 13: {  // DCT4x8 mode: 8x4 band matrix at (x, y / 2); DCT8x4 transposed
-      std::vector<double> w84 = band_weights(8, 4, kDist4x8, nullptr, c, 2);
+    case kDqDct4x8: {  // 8x4 band matrix at (x, y / 2); transposed for DCT8x4
+      std::vector<double> w84 = band_weights(8, 4, db, e.num_bands, eb, e.num_ecc_bands);
       for (int y = 0; y < 8; ++y)
         for (int x = 0; x < 8; ++x) {
-          const int u = s == 12 ? x : y, v = s == 12 ? y : x;  // 8-point, 4-point axis
+          const int u = s == 13 ? y : x, v = s == 13 ? x : y;  // the 8x4 matrix's column, row
           double wv = w84[(v / 2) * 8 + u];
-          if (u == 0 && v == 1) wv /= kDct4x8Mul[c];
+          if (u == 0 && v == 1) wv /= prm[0];
           at(w, x, y) = wv;
-          at(num, x, y) = scale_i(8, u) * scale_i(4, v / 2) / 64.0;
         }
       break;
     }
-    case 14: {  // AFV mode: 4x4 values, each covering a 2x2 cell group
-      std::vector<double> bands = cumulative(kAfvW[c][4], &kAfvW[c][5], 3);
+    case kDqAfv: {  // 4x4 values, each covering a 2x2 cell group
+      const double* aw = e.afv_weights[c];
+      std::vector<double> bands = cumulative(aw[4], aw + 5, 3);
       double w4[16];
-      w4[0] = kAfvW[c][0];
-      w4[4] = kAfvW[c][1];  // group (0, 1)
-      w4[1] = kAfvW[c][2];  // group (1, 0)
-      w4[5] = kAfvW[c][3];
+      w4[0] = aw[0];
+      w4[4] = aw[1];  // group (0, 1)
+      w4[1] = aw[2];  // group (1, 0)
+      w4[5] = aw[3];
       for (int i = 0; i < 16; ++i)
         if ((i & 3) >= 2 || i >= 8) w4[i] = interp(kAfvFreq[i] - kAfvLo, kAfvHi, bands);
       for (int y = 0; y < 8; ++y)
         for (int x = 0; x < 8; ++x) at(w, x, y) = w4[(y / 2) * 4 + x / 2];
-      at(w, 1, 0) *= kAfvMul[c][0];
-      at(w, 0, 1) *= kAfvMul[c][0];
-      at(w, 1, 1) *= kAfvMul[c][1];
-      break;  // numerators 1
+      at(w, 1, 0) *= prm[0];
+      at(w, 0, 1) *= prm[0];
+      at(w, 1, 1) *= prm[1];
+      break;
     }
-    case 3: {  // DCT4 mode: 4x4 band matrix, each entry covering 2x2
-      std::vector<double> w4 = band_weights(4, 4, kDist4, nullptr, c, 2);
+    case kDqDct4: {  // 4x4 band matrix, each entry covering 2x2
+      std::vector<double> w4 = band_weights(4, 4, db, e.num_bands, eb, e.num_ecc_bands);
       for (int y = 0; y < 8; ++y)
-        for (int x = 0; x < 8; ++x) {
-          at(w, x, y) = w4[(y / 2) * 4 + x / 2];
-          at(num, x, y) = scale_i(4, x / 2) * scale_i(4, y / 2) / 64.0;
-        }
-      at(w, 1, 0) /= kDct4Mul[c][0];
-      at(w, 0, 1) /= kDct4Mul[c][0];
-      at(w, 1, 1) /= kDct4Mul[c][1];
+        for (int x = 0; x < 8; ++x) at(w, x, y) = w4[(y / 2) * 4 + x / 2];
+      at(w, 1, 0) /= prm[0];
+      at(w, 0, 1) /= prm[0];
+      at(w, 1, 1) /= prm[1];
       break;
     }
-    default: {  // DCT mode
-      const BandSet* dist = nullptr;
-      const BandSet* ecc = nullptr;
-      int n_ecc = 3;
-      switch (s) {
-        case 0: dist = &kDist8; break;
-        case 4: dist = &kDist16; break;
-        case 5: dist = &kDist32; n_ecc = 4; break;
-        case 6: case 7: dist = &kDist16x8; break;
-        case 8: case 9: dist = &kDist32x8; ecc = &kEcc32x8; n_ecc = 4; break;
-        case 10: case 11: dist = &kDist32x16; n_ecc = 4; break;
-        default: return false;
-      }
-      w = band_weights(X, Y, *dist, ecc, c, n_ecc);
-      for (int y = 0; y < Y; ++y)
-        for (int x = 0; x < X; ++x) at(num, x, y) = scale_i(X, x) * scale_i(Y, y) / (double(X) * Y);
+    default:  // DCT mode, the varblock's own size
+      w = band_weights(X, Y, db, e.num_bands, eb, e.num_ecc_bands);
       break;
-    }
   }
+  // Numerators by transform type: 1 for Identity, DCT2 and AFV; otherwise
+  // I(N, f) per axis over X Y, with N = 4 and f = pos / 2 on an axis of
+  // 4-point transforms.
+  for (int y = 0; y < Y; ++y)
+    for (int x = 0; x < X; ++x) {
+      double v = 1.0;
+      if (s == 3) v = scale_i(4, x / 2) * scale_i(4, y / 2) / 64.0;
+      else if (s == 12) v = scale_i(8, x) * scale_i(4, y / 2) / 64.0;
+      else if (s == 13) v = scale_i(4, x / 2) * scale_i(8, y) / 64.0;
+      else if (s != 1 && s != 2 && s != 14) v = scale_i(X, x) * scale_i(Y, y) / (double(X) * Y);
+      at(num, x, y) = v;
+    }
   for (int i = 0; i < X * Y; ++i) {
     const double v = num[i] / w[i];
     if (i > 0 && !(v > 0.0 && std::isfinite(v))) return false;
@@ -439,11 +520,17 @@ void build_mfma_operands(DeviceTables* t) {
           t->mfma_a[m][0][step][l][e] = hi;
           t->mfma_a[m][1][step][l][e] = lo;
         }
+    for (int n = 0; n < 32; ++n)
+      for (int u = 0; u < 4; ++u)
+        t->llf_cos[m][n][u] =
+            n < N && u < N / 8 ? float(std::cos(pi * (2 * n + 1) * u / (2.0 * N))) : 0.0f;
+    for (int n = 0; n < 32; ++n)
+      t->llf_c1[m][n] = n < N ? float(std::cos(pi * (2 * n + 1) / (2.0 * N))) : 0.0f;
   }
 }
 }  // namespace
 
-bool build_tables(DeviceTables* t) {
+bool build_tables(DeviceTables* t, const DequantEncoding* enc) {
   std::memset(t, 0, sizeof(*t));
   std::vector<double> m(32 * 32);
   inverse_transform_matrix_f64(8, m.data());
@@ -596,7 +683,7 @@ bool build_tables(DeviceTables* t) {
   for (int s = 0; s < kNumStrategies; ++s) {
     const int X = 8 * blocks_x(s), Y = 8 * blocks_y(s), sz = X * Y;
     for (int c = 0; c < 3; ++c) {
-      if (!dequant_matrix_f64(s, c, dq.data())) return false;
+      if (!dequant_matrix_f64(s, c, dq.data(), enc)) return false;
       for (int i = 0; i < sz; ++i) {
         const int x = i % X, y = i / X;
         double sc = 1.0;

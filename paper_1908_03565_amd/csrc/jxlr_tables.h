@@ -80,6 +80,12 @@ struct DeviceTables {
   // A-operand order of a 32x32x16 matrix instruction: element e of lane l in
   // k-step t is A[l mod 32][16 t + 8 (l / 32) + e].
   alignas(16) uint16_t mfma_a[3][2][2][64][8];
+  // The same cosines in binary32 for the varblocks' LLF corners, which the
+  // split form transforms outside the matrix products: llf_cos[m][n][u] =
+  // cos(pi (2 n + 1) u / (2 N)), N = 8 << m, n < N, u < 4 (zero for u >= N / 8),
+  // and llf_c1[m][n] = llf_cos[m][n][1].
+  alignas(16) float llf_cos[3][32][4];
+  float llf_c1[3][32];
   // AFV basis (I.2.2): afv[j][i] = basis vector j at 4x4 index i.
   float afv[16][16];
   // Inverses of a16s and a32s: DC samples from the scaled LLF, one axis
@@ -112,12 +118,33 @@ struct DeviceTables {
   float jpeg1_a[8][8];
 };
 
-// Fills t on the host.  Returns false if a dequantization matrix entry is not
-// positive and finite (C.6.1).
-bool build_tables(DeviceTables* t);
+// Encoding of one dequantization matrix (C.6.1): the layout of the public
+// jxlr_dequant_encoding (checked where both are visible).
+enum DequantMode {
+  kDqLibrary = 0, kDqIdentity = 1, kDqDct2 = 2, kDqDct4 = 3, kDqDct4x8 = 4, kDqAfv = 5,
+  kDqDct = 6, kDqCopy = 7
+};
+struct DequantEncoding {
+  int32_t mode;
+  int32_t copy_from;
+  int32_t num_bands;
+  int32_t num_ecc_bands;
+  double dist_bands[3][17];
+  double ecc_bands[3][8];
+  double params[3][6];
+  double afv_weights[3][8];
+};
 
+// Fills t on the host, with the dequantization matrices of the encodings
+// enc[0..14] (indexed by transform type; null: the C.6.1.1 defaults).
+// Returns false if an encoding is not valid for its matrix or an entry is
+// not positive and finite (C.6.1).
+bool build_tables(DeviceTables* t, const DequantEncoding* enc = nullptr);
+
+// The C.6.1.1 default encoding of transform type s.
+void default_encoding(int s, DequantEncoding* out);
 // The same tables in double precision, for the host-side cross-checks.
-bool dequant_matrix_f64(int s, int c, double* out);
+bool dequant_matrix_f64(int s, int c, double* out, const DequantEncoding* enc = nullptr);
 void inverse_transform_matrix_f64(int n, double* out);
 // s_N(k): the draft's inverse transform is the plain DCT-III applied to
 // coefficients multiplied by s_N(k).

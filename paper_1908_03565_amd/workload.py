@@ -80,6 +80,38 @@ def strategy_map(rng, Wb, Hb, choices, p_dct32=None):
     return smap
 
 
+def mixed_tiling_map(rng, Wb, Hb, choices=None):
+    """DctSelect with several transform types inside each 32x32 region: the
+    region's blocks are visited in raster order (the order of C.5.4) and each
+    one not yet covered starts a varblock of a type drawn uniformly among
+    `choices` (default: all fifteen) whose varblock is naturally aligned there,
+    stays inside the region and the frame, and overlaps no earlier varblock.
+    Every block of a varblock holds its type."""
+    choices = ALL_TYPES if choices is None else list(choices)
+    smap = np.zeros((Hb, Wb), np.uint8)
+    for ry in range(0, Hb, 4):
+        for rx in range(0, Wb, 4):
+            nbx, nby = min(4, Wb - rx), min(4, Hb - ry)
+            covered = np.zeros((nby, nbx), bool)
+            for by in range(nby):
+                for bx in range(nbx):
+                    if covered[by, bx]:
+                        continue
+                    ok = []
+                    for s in choices:
+                        cx, cy = BLOCKS[s]
+                        if bx % cx or by % cy or bx + cx > nbx or by + cy > nby:
+                            continue
+                        if covered[by:by + cy, bx:bx + cx].any():
+                            continue
+                        ok.append(s)
+                    s = ok[rng.integers(len(ok))] if ok else DCT8
+                    cx, cy = BLOCKS[s]
+                    covered[by:by + cy, bx:bx + cx] = True
+                    smap[ry + by:ry + by + cy, rx + bx:rx + bx + cx] = s
+    return smap
+
+
 def _varblock_geometry(smap):
     """Per coefficient position: (x, y) inside its varblock and the varblock
     size in pixels, for a map produced by strategy_map."""
@@ -101,12 +133,18 @@ def _varblock_geometry(smap):
 
 
 def frame(W, H, seed, choices=None, p_dct32=None, qf_const=None, cfl_zero=False,
-          epf_iters=2, gab=1, out_format=0, name="frame"):
-    """One synthetic frame as a dict of numpy arrays plus parameter overrides."""
+          epf_iters=2, gab=1, out_format=0, name="frame", tiling="region"):
+    """One synthetic frame as a dict of numpy arrays plus parameter overrides.
+    tiling: "region" draws one transform type per 32x32 region
+    (strategy_map), "mixed" mixes types inside each region
+    (mixed_tiling_map over `choices`, default all fifteen)."""
     rng = np.random.default_rng(seed)
     Wb, Hb = (W + 7) // 8, (H + 7) // 8
-    choices = MIXED if choices is None else choices
-    smap = strategy_map(rng, Wb, Hb, choices, p_dct32)
+    if tiling == "mixed":
+        smap = mixed_tiling_map(rng, Wb, Hb, choices)
+    else:
+        choices = MIXED if choices is None else choices
+        smap = strategy_map(rng, Wb, Hb, choices, p_dct32)
 
     # DC: uniform integers in [-512, 512] per block and channel.
     dc = rng.integers(-512, 513, size=(3, Hb, Wb), dtype=np.int64).astype(np.int32)
