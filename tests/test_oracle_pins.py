@@ -521,6 +521,254 @@ def test_dequant_dct8_on_axis_last_band():
     assert O.dequant_matrix(0, 0)[0, 4] == pytest.approx(expect, rel=1e-12)
 
 
+# ---- C.6.1 encodings ------------------------------------------------------
+
+def _flat_dct(w=(2.0, 3.0, 5.0), nb=3, ne=1):
+    """A DCT-mode encoding whose weights are w[c] at every position: the
+    first distance band is w[c], every later one a factor 1 (encoded 0), and
+    the eccentricity bands are 1."""
+    return {"mode": 6, "num_bands": nb, "num_ecc_bands": ne,
+            "dist_bands": [[w[c]] + [0.0] * (nb - 1) for c in range(3)],
+            "ecc_bands": [[0.0] * ne for _ in range(3)]}
+
+
+def _lib15():
+    return [{"mode": 0} for _ in range(15)]
+
+
+def test_library_and_explicit_defaults_give_the_default_matrices():
+    # Library mode stands for the C.6.1.1 encoding; that encoding written out
+    # in its own mode gives the same matrices (the defaults are pinned above)
+    for s in range(15):
+        bx, by = O.varblock_size(s)
+        explicit = _lib15()
+        explicit[s] = O.default_encoding(s)
+        assert explicit[s]["mode"] != 0
+        for c in range(3):
+            ref = O.dequant_matrix(s, c)
+            np.testing.assert_array_equal(O.dequant_matrix(s, c, _lib15()), ref)
+            np.testing.assert_array_equal(O.dequant_matrix(s, c, explicit), ref)
+
+
+def test_copy_mode_takes_an_earlier_encoding_for_the_current_type():
+    enc = _lib15()
+    enc[6] = {"mode": 6, "num_bands": 4, "num_ecc_bands": 2,
+              "dist_bands": [[3.0, -0.5, 0.2, -1.0]] * 3, "ecc_bands": [[0.3, -0.2]] * 3}
+    enc[7] = {"mode": 7, "copy_from": 6}      # DCT8x16 copies DCT16x8's encoding
+    enc[11] = {"mode": 7, "copy_from": 7}     # a copy of a copy
+    enc[4] = {"mode": 7, "copy_from": 0}      # DCT16 copies DCT8, which is Library
+    for c in range(3):
+        # the band procedure is symmetric under exchanging the axes, and so
+        # are the numerators: the copied encoding gives the transpose
+        np.testing.assert_allclose(O.dequant_matrix(7, c, enc), O.dequant_matrix(6, c, enc).T,
+                                   rtol=1e-14)
+        # DCT16x32 evaluates DCT16x8's encoding at 16 x 32
+        e11 = _lib15()
+        e11[11] = dict(enc[6])
+        np.testing.assert_array_equal(O.dequant_matrix(11, c, enc), O.dequant_matrix(11, c, e11))
+        # DCT16 from DCT8's default encoding (DCT mode, its bands) at 16 x 16
+        e4 = _lib15()
+        e4[4] = O.default_encoding(0)
+        np.testing.assert_array_equal(O.dequant_matrix(4, c, enc), O.dequant_matrix(4, c, e4))
+        assert not np.allclose(O.dequant_matrix(4, c, enc), O.dequant_matrix(4, c))
+    bad = _lib15()
+    bad[5] = {"mode": 7, "copy_from": 5}      # not an earlier matrix
+    with pytest.raises(O.OracleError):
+        O.dequant_matrix(5, 0, bad)
+    bad[5] = {"mode": 7, "copy_from": 0}
+    bad[0] = {"mode": 7, "copy_from": 0}
+    with pytest.raises(O.OracleError):
+        O.dequant_matrix(0, 0, bad)
+
+
+def test_dct_mode_two_bands_is_a_geometric_ramp():
+    # two distance bands b0, b0 f(v) and one eccentricity band 1, f(e): the
+    # geometric interpolation makes the weight b0 f(v)^(dist / sqrt 2)
+    # f(e)^ecc, with dist = |(x / X, y / Y)| and ecc = |x / X - y / Y| / dist
+    f = lambda v: v + 1 if v > 0 else 1 / (1 - v)
+    for s in (0, 4, 6, 10):
+        bx, by = O.varblock_size(s)
+        enc = _lib15()
+        enc[s] = {"mode": 6, "num_bands": 2, "num_ecc_bands": 1,
+                  "dist_bands": [[2.0, -0.5], [1.5, 0.7], [0.8, -2.0]],
+                  "ecc_bands": [[0.4], [-0.3], [1.1]]}
+        for c in range(3):
+            b0, v = enc[s]["dist_bands"][c]
+            e = enc[s]["ecc_bands"][c][0]
+            m = O.dequant_matrix(s, c, enc)
+            x = np.arange(bx)[None, :] / bx
+            y = np.arange(by)[:, None] / by
+            dist = np.sqrt(x * x + y * y)
+            with np.errstate(invalid="ignore", divide="ignore"):
+                ecc = np.where(dist > 0, np.abs(x - y) / dist, 0.0)
+            w = b0 * f(v) ** (dist / math.sqrt(2)) * f(e) ** ecc
+            num = np.array([[O.scale_I(bx, i) * O.scale_I(by, j) / (bx * by) for i in range(bx)]
+                            for j in range(by)])
+            np.testing.assert_allclose(m.ravel()[1:], (num / w).ravel()[1:], rtol=1e-12)
+
+
+@pytest.mark.parametrize("s", [0, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13])
+def test_flat_weight_numerators_give_every_coefficient_the_same_energy(s):
+    # C.6.1 numerators are built from I(N, u) of I.2.6.1, which makes each
+    # inverse transform orthonormal once its coefficients are multiplied by
+    # I: under flat weights (the same value at every position) a unit
+    # quantized coefficient at any position decodes to a pixel block of the
+    # same L2 energy.  The exceptions are the positions the printed steps
+    # combine before the 4-point transforms: the 2 x 2 corner of DCT4 (the
+    # AuxIDCT2x2 step, energy gain 4) and the DC pair of DCT4x8 / DCT8x4
+    # (sum and difference, gain 2).  Swapping the axes of a non-square
+    # numerator, or using the 8-point factor on a 4-point dimension, breaks
+    # the equality.
+    bx, by = O.varblock_size(s)
+    enc = [_flat_dct() for _ in range(15)]
+    for c in range(3):
+        D = O.dequant_matrix(s, c, enc)
+        E = np.zeros((by, bx))
+        for y in range(by):
+            for x in range(bx):
+                K = np.zeros((by, bx))
+                K[y, x] = 1.0
+                E[y, x] = D[y, x] ** 2 * (O.inverse_transform(s, K) ** 2).sum()
+        gain = np.ones((by, bx))
+        if s == 3:
+            gain[0:2, 0:2] = 4.0
+        elif s == 12:
+            gain[0:2, 0] = 2.0
+        elif s == 13:
+            gain[0, 0:2] = 2.0
+        np.testing.assert_allclose(E / gain, E[-1, -1], rtol=1e-12)
+
+
+def test_identity_dct2_dct4_afv_modes_place_their_parameters():
+    enc = _lib15()
+    idp = [[100.0, 200.0, 300.0], [10.0, 20.0, 30.0], [1.0, 2.0, 3.0]]
+    d2p = [[11.0, 12.0, 13.0, 14.0, 15.0, 16.0]] * 3
+    enc[1] = {"mode": 1, "params": idp}
+    enc[0] = {"mode": 1, "params": idp}          # Identity mode for the DCT8 matrix
+    enc[2] = {"mode": 2, "params": d2p}
+    enc[3] = dict(_flat_dct(), mode=3, params=[[2.0, 4.0]] * 3)
+    enc[14] = {"mode": 5, "params": [[2.0, 3.0]] * 3,
+               "afv_weights": [[10.0, 20.0, 30.0, 40.0, 50.0, 0.0, 0.0, 0.0]] * 3}
+    for c in range(3):
+        m = O.dequant_matrix(1, c, enc)           # numerators 1
+        assert m[1, 1] == 1 / idp[c][2] and m[0, 1] == m[1, 0] == 1 / idp[c][1]
+        assert np.all(m[2:, :] == 1 / idp[c][0]) and np.all(m[:, 2:] == 1 / idp[c][0])
+        m0 = O.dequant_matrix(0, c, enc)          # the DCT8 numerators over the same weights
+        num8 = np.array([[O.scale_I(8, i) * O.scale_I(8, j) / 64 for i in range(8)] for j in range(8)])
+        np.testing.assert_allclose(m0, num8 * m, rtol=1e-14)
+        m = O.dequant_matrix(2, c, enc)
+        np.testing.assert_array_equal(m, m.T)
+        expect = {(0, 1): 11, (1, 1): 12, (2, 0): 13, (3, 1): 13, (2, 2): 14, (3, 3): 14,
+                  (4, 0): 15, (7, 3): 15, (4, 4): 16, (7, 7): 16}
+        for (x, y), v in expect.items():
+            assert m[y, x] == 1 / v
+        m = O.dequant_matrix(3, c, enc)           # flat weights 2, 3, 5 with the 2x2 corner divided
+        wc = [2.0, 3.0, 5.0][c]
+        num4 = np.array([[O.scale_I(4, i // 2) * O.scale_I(4, j // 2) / 64 for i in range(8)]
+                         for j in range(8)])
+        w = np.full((8, 8), wc)
+        w[0, 1] = w[1, 0] = wc / 2.0
+        w[1, 1] = wc / 4.0
+        np.testing.assert_allclose(m.ravel()[1:], (num4 / w).ravel()[1:], rtol=1e-14)
+        m = O.dequant_matrix(14, c, enc)
+        assert np.all(m[0:2, 2:4] == 1 / 30.0) and np.all(m[2:4, 0:2] == 1 / 20.0)
+        assert m[0, 1] == m[1, 0] == 1 / (10.0 * 2.0) and m[1, 1] == 1 / (10.0 * 3.0)
+        assert np.all(m[2:4, 2:4] == 1 / 40.0)
+        np.testing.assert_allclose(m[4:, 4:], 1 / 50.0, rtol=1e-14)   # band factors 1
+
+
+def test_ill_formed_encodings_are_rejected():
+    def fails(s, e):
+        enc = _lib15()
+        enc[s] = e
+        with pytest.raises(O.OracleError):
+            O.dequant_matrix(s, 0, enc)
+    fails(4, {"mode": 1, "params": [[1.0, 1.0, 1.0]] * 3})     # Identity mode, 256 entries
+    fails(5, {"mode": 5, "params": [[1.0, 1.0]] * 3, "afv_weights": [[1.0] * 8] * 3})
+    fails(0, dict(_flat_dct(), num_bands=18))
+    fails(0, dict(_flat_dct(), num_ecc_bands=0))
+    fails(0, _flat_dct(w=(-1.0, -1.0, -1.0)))                 # non-positive entries
+    fails(0, {"mode": 6, "num_bands": 2, "num_ecc_bands": 1,   # an infinite band
+              "dist_bands": [[1.0, np.inf]] * 3, "ecc_bands": [[0.0]] * 3})
+    fails(0, _flat_dct(w=(5e-324,) * 3))                      # entries overflow to inf
+    fails(1, {"mode": 1, "params": [[0.0, 1.0, 1.0]] * 3})     # division by zero
+    fails(0, {"mode": 8})
+
+
+# ---- C.5.2 DcQuantField ---------------------------------------------------
+
+def test_dc_smoothing_reads_each_samples_dequantization_range():
+    # a 5 x 5 DC image, constant 3 but for a bump b at (2, 2); the 3x3 weights
+    # sum to 1, so the average is 3 + wc b, b (1 - wc) = 0.4 below the
+    # sample.  The centre is smoothed when its own field value is 1
+    # (0.4 < 0.5) and kept when it is 1/2 (0.4 > 0.25); the neighbours'
+    # field values do not matter
+    q = O.params(40, 40, dc_mul=(1.0, 1.0, 1.0), extra_levels=(1, 1, 1), dc_smoothing=1)
+    wc = 0.05226273532324128
+    b = 0.4 / (1.0 - wc)
+    d = np.full((3, 5, 5), 3.0)
+    d[:, 2, 2] += b
+    for centre, smoothed in ((1.0, True), (0.5, False)):
+        fld = np.full((3, 5, 5), 0.25, np.float32)
+        fld[:, 2, 2] = centre
+        out = O.dc_smooth(q, d, fld)
+        expect = 3.0 + wc * b if smoothed else 3.0 + b
+        assert out[1, 2, 2] == pytest.approx(expect, abs=1e-12)
+    # without a field: dc_mul / 2^extra_levels = 0.5, so the bump stays
+    assert O.dc_smooth(q, d)[1, 2, 2] == pytest.approx(3.0 + b, abs=1e-15)
+
+
+def test_qco_clamps_each_dc_sample_to_its_own_range():
+    # one DCT16 varblock (2 x 2 DC samples) with an LF-only residual of 1.0
+    # in each DC sample; the field allows 0.3, 0.6, 0.9 and 1.2 times 1/mul
+    s = 4
+    W = H = 16
+    f = _qco_frame(s, W, H, qf=1)
+    q = O.params(W, H, qco=1, qco_interval_mul=0.5, epf_iters=1)
+    llf = O.llf_from_dc(s, np.ones((2, 2)))
+    K = np.zeros((16, 16))
+    K[:2, :2] = llf
+    R = O.inverse_transform(s, K)
+    orig = np.zeros((3, H, W))
+    filt = np.repeat(R[None], 3, axis=0)
+    fld = np.zeros((3, 2, 2), np.float32)
+    fld[:] = np.array([[0.6, 1.2], [1.8, 2.4]], np.float32)
+    f2 = dict(f, dc_quant=fld)
+    out = O.qco(q, f2, orig, filt)
+    for c in range(3):
+        Kc = O.forward_transform(s, out[c]) / 256.0
+        D = O.dc_from_llf(s, Kc[:2, :2])
+        np.testing.assert_allclose(D, np.minimum(1.0, 0.5 * fld[c].astype(np.float64)), atol=1e-12)
+
+
+def test_ac_prediction_window_is_the_dc_multiplier_not_the_field():
+    # Annex H's 1.7 dcq window uses the channel's DC multiplier: the image
+    # step is the same with extra_levels 0 and 3 and ignores the field
+    rng = _rng(31)
+    Hb, Wb = 6, 7
+    strategy = np.zeros((Hb, Wb), np.uint8)
+    d = rng.uniform(-2, 2, size=(3, Hb, Wb))
+    q0 = O.params(8 * Wb, 8 * Hb, dc_mul=(1.0, 1.0, 1.0))
+    q3 = O.params(8 * Wb, 8 * Hb, dc_mul=(1.0, 1.0, 1.0), extra_levels=(3, 3, 3))
+    a = O.ac_prediction_image(q0, strategy, d)
+    b = O.ac_prediction_image(q3, strategy, d)
+    np.testing.assert_array_equal(a, b)
+    fld = np.full((3, Hb, Wb), 0.01, np.float32)
+    q3.dc_quant_field = fld.ctypes.data
+    np.testing.assert_array_equal(O.ac_prediction_image(q3, strategy, d), a)
+    q3.dc_quant_field = None
+
+
+def test_field_values_must_be_positive_and_finite():
+    q = O.params(16, 16)
+    frame = _frame_of(0, 16, 16, np.zeros((3, 2, 2), np.int32))
+    for bad in (0.0, -1.0, np.inf, np.nan):
+        fld = np.ones((3, 2, 2), np.float32)
+        fld[1, 1, 0] = bad
+        with pytest.raises(O.OracleError):
+            O.reconstruct(q, dict(frame, dc_quant=fld))
+
+
 def test_ac_dequant_bias_and_cfl_linearity():
     # One DCT8 varblock with a single Y coefficient q: X gets kX times the Y
     # image, B gets kB times it (Annex G), and the Y amplitude follows the
