@@ -73,6 +73,39 @@ typedef enum { JXLR_OUT_F32 = 0, JXLR_OUT_U8_SRGB = 1, JXLR_OUT_U16_SRGB = 2 } j
 
 #define JXLR_MAX_DIM 65536u
 
+/* Encoding modes of a dequantization matrix (C.6.1). */
+typedef enum {
+  JXLR_DQ_LIBRARY = 0, JXLR_DQ_IDENTITY = 1, JXLR_DQ_DCT2 = 2, JXLR_DQ_DCT4 = 3,
+  JXLR_DQ_DCT4X8 = 4, JXLR_DQ_AFV = 5, JXLR_DQ_DCT = 6, JXLR_DQ_COPY = 7
+} jxlr_dequant_mode;
+
+/* One dequantization matrix's encoding (C.6.1), already read from the
+ * stream (the F16 parameters as their values).  Fields a mode does not read
+ * are ignored.  Per channel X, Y, B:
+ *   LIBRARY   the C.6.1.1 default encoding of this matrix;
+ *   IDENTITY  params[c][0..2];             DCT2  params[c][0..5];
+ *   DCT4      params[c][0..1] and the bands;
+ *   DCT4X8    params[c][0] (dct4x8multipliers) and the bands;
+ *   AFV       params[c][0..1] (dct4multipliers), afv_weights[c][0..7];
+ *   DCT       the bands;
+ *   COPY      the encoding of matrix copy_from, which must be smaller than
+ *             this matrix's index (evaluated for this matrix's type).
+ * Bands: num_bands distance bands dist_bands[c][0..num_bands-1], 2..17, and
+ * num_ecc_bands eccentricity bands ecc_bands[c][0..num_ecc_bands-1], 1..8.
+ * IDENTITY, DCT2, DCT4, DCT4X8 and AFV define 64-entry matrices only (types
+ * DCT8, IDENTITY, DCT2, DCT4, DCT4X8, DCT8X4, AFV); DCT4X8 is transposed for
+ * DCT8X4. */
+typedef struct {
+  int32_t mode;
+  int32_t copy_from;
+  int32_t num_bands;
+  int32_t num_ecc_bands;
+  double  dist_bands[3][17];
+  double  ecc_bands[3][8];
+  double  params[3][6];
+  double  afv_weights[3][8];
+} jxlr_dequant_encoding;
+
 /* Decoded frame-header fields.  Channel order X, Y, B.  jxlr_params_default
  * fills the draft's defaults. */
 typedef struct {
@@ -106,25 +139,25 @@ typedef struct {
    * kSkipAdaptiveDCSmoothing case): each dequantized DC sample away from the
    * frame's first and last block row and column becomes the 3x3 weighted
    * average of its neighbourhood when that lies within 0.5 dcq of it, dcq =
-   * dc_mul[c] (the DcQuantField of C.5.2 with extra_levels 0, which smoothing
-   * therefore requires: JXLR_E_PARAM otherwise).  Applied before the DC chroma
-   * from luma and the LLF computation. */
+   * the sample's DcQuantField (C.5.2; io->dc_quant, or dc_mul[c] /
+   * 2^extra_levels[c] without it).  Applied before the DC chroma from luma
+   * and the LLF computation. */
   int32_t  dc_smoothing;
   /* Quantization constraint of J.3 (loop_filter.qco, default 0), applied once
    * after the last EPF pass (none without EPF): per varblock and channel the
    * residual of the filter passes is transformed to coefficients, each
    * clamped to +-qco_interval_mul quantization steps (dequantization weight
-   * times AcMul; for the LLF corner, its DC samples to +-qco_interval_mul *
-   * dc_mul[c], which again requires extra_levels 0), and transformed back.
-   * The batch functions reject it (JXLR_E_PARAM). */
+   * times AcMul; for the LLF corner, each of its DC samples to
+   * +-qco_interval_mul times that sample's DcQuantField), and transformed
+   * back.  The batch functions reject it (JXLR_E_PARAM). */
   int32_t  qco;
   float    qco_interval_mul;  /* C.10 default 0.5; finite, >= 0 */
   /* AC prediction of Annex H (1) or not (0, the default; the draft's
    * kSkipPredictLF case): per group of 256x256 samples an image of 2x2 cells
    * per block (I.2.6 at N = 4 of each varblock's LLF, a border from the DC
    * ring around the group, mirrored at the frame edge), adaptively smoothed
-   * (0.12 / 0.2 / 0.02 weights, accepted within 1.7 dc_mul[c]; extra_levels
-   * must be 0), then I.2.7 at N = 4 gives each varblock's top 2cy x 2cx
+   * (0.12 / 0.2 / 0.02 weights, accepted within 1.7 dc_mul[c], the DC
+   * multiplier of C.4.1 itself), then I.2.7 at N = 4 gives each varblock's top 2cy x 2cx
    * coefficients, which are added (LLF corner excepted) after the chroma
    * from luma.  Needs io->ac_pred for jxlr_reconstruct (filled by
    * jxlr_ac_prediction); jxlr_decode manages it.  The batch functions reject
@@ -223,6 +256,16 @@ typedef struct {
   const int32_t* spline_offsets;
   const int32_t* spline_points;
   const float* spline_dct;
+  /* C.5.2 DcQuantField per channel, float [Hb][Wb], row stride
+   * dc_quant_stride elements: the dequantization range of each DC sample
+   * (dc_mul[c] / 2^k for the k its decoded delta gives), which the F.2
+   * smoothing and the J.3 LLF clamp read.  All three NULL: dc_mul[c] /
+   * 2^extra_levels[c] everywhere (the field of a plane whose deltas are all
+   * 0; with extra_levels 0 the field whatever the deltas).  Entries must be
+   * positive and finite; the library reads them only with dc_smoothing or
+   * the quantization constraint on. */
+  const float* dc_quant[3];
+  size_t dc_quant_stride;
 } jxlr_frame_io;
 
 typedef struct jxlr_ctx jxlr_ctx;
@@ -235,11 +278,33 @@ const char* jxlr_status_string(jxlr_status s);
  * x/b_factor_dc = 128, Gaborish on, one EPF pass, F32 output. */
 jxlr_status jxlr_params_default(jxlr_frame_params* p, uint32_t xsize, uint32_t ysize);
 
-/* Creates a context on HIP device `device`: builds the default dequantization
- * matrices (C.6.1.1), transform matrices (I.2.1, I.2.6), LLF tables (I.2.7)
- * and the EPF mul_table (J.2.4) on the host and uploads them. */
-jxlr_status jxlr_create(jxlr_ctx** ctx, int device);
+/* Creates a context on HIP device `device`: builds the dequantization
+ * matrices (C.6.1) of the encodings dq[0..14] (a host array indexed by
+ * transform type, C.5.4 numbering; NULL: the C.6.1.1 defaults), the
+ * transform matrices (I.2.1, I.2.6), LLF tables (I.2.7) and the EPF
+ * mul_table (J.2.4) on the host and uploads them.  The encodings are read
+ * only during the call.  JXLR_E_DEQUANT: an encoding not valid for its
+ * matrix (mode out of range, a 64-entry mode for a larger matrix, band
+ * counts out of range, a Copy that does not name an earlier matrix) or a
+ * matrix entry that is not positive and finite; JXLR_E_HIP: device
+ * allocation or upload failed. */
+jxlr_status jxlr_create(jxlr_ctx** ctx, int device, const jxlr_dequant_encoding* dq);
 void jxlr_destroy(jxlr_ctx* ctx);
+
+/* Annex G: the chroma-from-luma factors of n u8 XFromY / BFromY values
+ * (C.5.3, or x_factor_dc / b_factor_dc of C.4.3): kx[i] = (x_factor[i] -
+ * 128) / 256, kb[i] = 0.935669 + (b_factor[i] - 128) / 128.  Host arrays;
+ * either pair may be NULL to skip it. */
+jxlr_status jxlr_cfl_from_u8(const uint8_t* x_factor, const uint8_t* b_factor, size_t n,
+                             float* kx, float* kb);
+
+/* C.4.1: the DC multipliers mX_DC, mY_DC, mB_DC = weight[c] / (global_scale
+ * * quant_dc), with weights NULL for the defaults {4096, 512, 256},
+ * global_scale = global_scale_minus_1 + 1 (1..65536) and quant_dc =
+ * quant_dc_minus_1 + 1 (C.4.2, >= 1).  JXLR_E_PARAM for zero sizes or a
+ * weight that is not positive and finite. */
+jxlr_status jxlr_dc_mul_from_header(const float* weights, uint32_t global_scale,
+                                    uint32_t quant_dc, float dc_mul[3]);
 
 /* Host-side check of host copies of the maps against C.5.4 (every varblock
  * type supported, naturally aligned, inside the frame, no overlap) and C.5.5

@@ -2149,6 +2149,55 @@ int orc_jpeg1_component(const int32_t* qcoef, int32_t wib, int32_t hib, const in
   return ORC_OK;
 }
 
+/* M.6.3: the side channel's block-gated Gaborish on one component's pixels
+ * [8 hib][8 wib] (the output of M.6.2), in place.  code: the four decoded
+ * bytes gab_weight1 * 1024, gab_weight2 * 1024, threshold * 16 and limit.
+ * The smoothed plane is the J.4 convolution (centre 1, edge neighbours
+ * gab_weight1, diagonal ones gab_weight2, normalized to sum 1) of the
+ * pixels, mirrored (6.5) at the plane's edges; every 8 x 8 block takes the
+ * smoothed values when fewer than `limit` of its 6 x 6 interior pixels
+ * (offsets 1..6 both ways) differ from them by more than the threshold,
+ * and keeps its own otherwise.  Reading: the plane is the component's
+ * block-padded plane, as for the upsampling. */
+int orc_jpeg1_gaborish(double* pix, int32_t wib, int32_t hib, const uint8_t* code) {
+  if (wib < 1 || hib < 1) return ORC_E_SIZE;
+  const int32_t W = 8 * wib, H = 8 * hib;
+  const double w1 = code[0] / 1024.0, w2 = code[1] / 1024.0;
+  const double thr = code[2] / 16.0;
+  const int limit = code[3];
+  const double norm = 1.0 + 4.0 * w1 + 4.0 * w2;
+  double* sm = (double*)malloc(sizeof(double) * (size_t)W * H);
+  if (!sm) return ORC_E_SIZE;
+  for (int32_t y = 0; y < H; ++y)
+    for (int32_t x = 0; x < W; ++x) {
+      double acc = 0.0;
+      for (int dy = -1; dy <= 1; ++dy)
+        for (int dx = -1; dx <= 1; ++dx) {
+          const int taxi = abs(dx) + abs(dy);
+          const double w = taxi == 0 ? 1.0 : (taxi == 1 ? w1 : w2);
+          acc += w / norm * pix[(size_t)mirror(y + dy, H) * W + mirror(x + dx, W)];
+        }
+      sm[(size_t)y * W + x] = acc;
+    }
+  for (int32_t by = 0; by < hib; ++by)
+    for (int32_t bx = 0; bx < wib; ++bx) {
+      int count = 0;
+      for (int v = 1; v < 7; ++v)
+        for (int u = 1; u < 7; ++u) {
+          const size_t o = (size_t)(8 * by + v) * W + 8 * bx + u;
+          if (fabs(pix[o] - sm[o]) > thr) ++count;
+        }
+      if (count < limit)
+        for (int v = 0; v < 8; ++v)
+          for (int u = 0; u < 8; ++u) {
+            const size_t o = (size_t)(8 * by + v) * W + 8 * bx + u;
+            pix[o] = sm[o];
+          }
+    }
+  free(sm);
+  return ORC_OK;
+}
+
 /* M.6.4: linear 2x upsampling of n samples with respect to pixel centres,
  * mirrored at both ends (index -1 reads index 1, index n reads n - 2):
  * out[2i] = 3/4 a[i] + 1/4 a[i - 1], out[2i + 1] = 3/4 a[i] + 1/4 a[i + 1],

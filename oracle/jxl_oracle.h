@@ -249,6 +249,10 @@ int orc_decode_features(const orc_params* p,
  * out [8 hib][8 wib]. */
 int orc_jpeg1_component(const int32_t* qcoef, int32_t wib, int32_t hib, const int32_t* quant,
                         double* out);
+/* M.6.3 block-gated Gaborish of one component's pixels [8 hib][8 wib], in
+ * place; code: gab_weight1 * 1024, gab_weight2 * 1024, threshold * 16,
+ * limit (the side channel's four bytes). */
+int orc_jpeg1_gaborish(double* pix, int32_t wib, int32_t hib, const uint8_t* code);
 /* M.6.4 linear 2x upsampling of n samples (mirrored ends), strided. */
 void orc_upsample2(const double* in, int32_t n, size_t stride_in, double* out,
                    size_t stride_out);

@@ -139,6 +139,7 @@ def lib():
                                           C.c_void_p, _f64p]
         L.orc_dots.argtypes = [P, _i32p, C.c_int32, _f64p]
         L.orc_jpeg1_component.argtypes = [_i32p, C.c_int32, C.c_int32, _i32p, _f64p]
+        L.orc_jpeg1_gaborish.argtypes = [_f64p, C.c_int32, C.c_int32, _u8p]
         L.orc_upsample2.argtypes = [_f64p, C.c_int32, C.c_size_t, _f64p, C.c_size_t]
         L.orc_upsample2.restype = None
         L.orc_jpeg1_rasterize.argtypes = [C.c_int32, C.c_void_p * 3, _i32p, _i32p, _i32p, _i32p,
@@ -502,6 +503,16 @@ def jpeg1_component(qcoef, quant):
     return out
 
 
+def jpeg1_gaborish(pix, code):
+    """M.6.3 on one component's pixels [8 hib][8 wib]; code: the side
+    channel's four bytes (weight1 * 1024, weight2 * 1024, threshold * 16,
+    limit).  Returns the filtered plane."""
+    out = np.array(pix, dtype=np.float64, order="C", copy=True)
+    _check(lib().orc_jpeg1_gaborish(out, out.shape[1] // 8, out.shape[0] // 8,
+                                    np.ascontiguousarray(code, np.uint8)))
+    return out
+
+
 def upsample2(a):
     """M.6.4 on a 1-D array."""
     a = np.ascontiguousarray(a, np.float64)
@@ -525,8 +536,12 @@ def jpeg1_rasterize(pixels, hs, vs, xsize, ysize):
 
 
 def jpeg1_decode(j):
-    """Whole M.6 path of a synthetic JPEG1 frame dict (see workload.jpeg1)."""
+    """Whole M.6 path of a synthetic JPEG1 frame dict (see workload.jpeg1);
+    with j["gab"] (one four-byte code per component) the M.6.3 side
+    channel is applied."""
     pix = [jpeg1_component(c, q) for c, q in zip(j["coef"], j["quant"])]
+    if j.get("gab") is not None:
+        pix = [jpeg1_gaborish(p_, g) for p_, g in zip(pix, j["gab"])]
     return jpeg1_rasterize(pix, j["hs"], j["vs"], j["xsize"], j["ysize"])
 
 

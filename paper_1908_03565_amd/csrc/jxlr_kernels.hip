@@ -275,10 +275,13 @@ __device__ inline void afv_inverse(float* base, int ld, const float (*__restrict
 // F.2: the dequantized DC of block (bx, by) (plane offset d; `in`: inside the
 // frame), adaptively smoothed from its unsmoothed 3x3 neighbourhood when
 // `smooth` and the block is not on the frame's border (read from the planes),
-// then Annex G with the DC factors; out = X, Y, B.
+// then Annex G with the DC factors; out = X, Y, B.  The smoothing window is
+// 0.5 times the sample's DcQuantField (C.5.2): dcq[c] at (bx, by), or dc_mul
+// (the multiplier over 2^extra_levels) when dcq[0] is null.
 __device__ __attribute__((always_inline)) inline void block_dc(
     const int32_t* const (&dc)[3], size_t dc_stride, int Wb, int Hb, const float (&dc_mul)[3],
-    int smooth, float kx_dc, float kb_dc, int bx, int by, bool in, size_t d, float (&out)[3]) {
+    const float* const (&dcq)[3], size_t dcq_stride, int smooth, float kx_dc, float kb_dc,
+    int bx, int by, bool in, size_t d, float (&out)[3]) {
   const float dv0 = float(dc[0][d]), dv1 = float(dc[1][d]), dv2 = float(dc[2][d]);
   float x_ = dc_mul[0] * dv0, y_ = dc_mul[1] * dv1, b_ = dc_mul[2] * dv2;
   if (smooth && in && bx > 0 && by > 0 && bx + 1 < Wb && by + 1 < Hb) {
@@ -290,7 +293,8 @@ __device__ __attribute__((always_inline)) inline void block_dc(
       const int32_t* p2 = dc[c] + d + dc_stride;
       const float e = float(p0[0]) + float(p1[-1]) + float(p1[1]) + float(p2[0]);
       const float g = float(p0[-1]) + float(p0[1]) + float(p2[-1]) + float(p2[1]);
-      const float sv = *v[c], q = dc_mul[c];
+      const float sv = *v[c];
+      const float q = dcq[0] ? dcq[c][size_t(by) * dcq_stride + bx] : dc_mul[c];
       const float wa = fmaf(0.05226273532324128f, sv,
                             q * fmaf(0.20345139757231578f, e, 0.0334829185968739f * g));
       if (sv - 0.5f * q <= wa && wa <= sv + 0.5f * q) *v[c] = wa;
@@ -322,7 +326,9 @@ struct ReconArgs {
   int* status;
   const DeviceTables* __restrict__ tab;
   int split;        // split-precision matrix-core transform of uniform regions
-  int dc_smooth;    // adaptive DC smoothing (F.2); dcq = dc_mul
+  int dc_smooth;    // adaptive DC smoothing (F.2)
+  const float* dcq[3];  // DcQuantField planes (C.5.2), or null: dc_mul
+  size_t dcq_stride;
   const float* pred;  // AC prediction sums [3][2 Hb][2 Wb] (Annex H), or null
   int ac_vec;       // AC planes and stride allow 16-byte loads
   int xyb_vec;      // XYB planes and stride allow 16-byte stores
@@ -735,8 +741,8 @@ __device__ __attribute__((always_inline)) inline void recon_tile(const ReconArgs
     const size_t d = in ? size_t(by) * a.dc_stride + bx : 0;
     const float qfv = float(1 + a.qf[m]);
     float v3[3];
-    block_dc(a.dc, a.dc_stride, a.Wb, a.Hb, a.dc_mul, a.dc_smooth, a.kx_dc, a.kb_dc, bx, by, in, d,
-             v3);
+    block_dc(a.dc, a.dc_stride, a.Wb, a.Hb, a.dc_mul, a.dcq, a.dcq_stride, a.dc_smooth, a.kx_dc,
+             a.kb_dc, bx, by, in, d, v3);
     // C.5.5: AcMul = 2^16 / (global_scale * (1 + dv)); the product is an
     // integer below 2^24, so one rounding.
     s_acmul[tid] = in ? 65536.0f / (a.gscale * qfv) : 0.0f;
@@ -899,7 +905,10 @@ struct PredArgs {
   const int32_t* dc[3];
   size_t dc_stride;
   const uint8_t* info;
-  float dc_mul[3];
+  float dc_mul[3];  // DC dequantization: the multiplier over 2^extra_levels
+  float h_mul[3];   // the cells' smoothing window: the multiplier itself
+  const float* dcq[3];  // DcQuantField planes for the F.2 smoothing, or null
+  size_t dcq_stride;
   float kx_dc, kb_dc;
   int dc_smooth;
   float* pred;  // [3][2 Hb][2 Wb]
@@ -931,8 +940,8 @@ __global__ __launch_bounds__(kPredThreads) void acpred_kernel(PredArgs a, int gr
     const int ly = i / rw, lx = i - ly * rw;
     const int bx = mirror(gx0 - 1 + lx, a.Wb), by = mirror(gy0 - 1 + ly, a.Hb);
     float v[3];
-    block_dc(a.dc, a.dc_stride, a.Wb, a.Hb, a.dc_mul, a.dc_smooth, a.kx_dc, a.kb_dc, bx, by, true,
-             size_t(by) * a.dc_stride + bx, v);
+    block_dc(a.dc, a.dc_stride, a.Wb, a.Hb, a.dc_mul, a.dcq, a.dcq_stride, a.dc_smooth, a.kx_dc,
+             a.kb_dc, bx, by, true, size_t(by) * a.dc_stride + bx, v);
     s_gdc[ly][lx] = c == 0 ? v[0] : c == 1 ? v[1] : v[2];
   }
   __syncthreads();
@@ -989,7 +998,7 @@ __global__ __launch_bounds__(kPredThreads) void acpred_kernel(PredArgs a, int gr
   const int cw = 2 * gw, ncell = cw * 2 * gh;
   constexpr int kCellsPerThread = (2 * kGroupBlocks) * (2 * kGroupBlocks) / kPredThreads;
   {
-    const float q = a.dc_mul[c];
+    const float q = a.h_mul[c];
     float nv[kCellsPerThread];
 #pragma unroll
     for (int k = 0; k < kCellsPerThread; ++k) {
@@ -1259,7 +1268,9 @@ struct QcoArgs {
   size_t stride;
   float gscale;       // global_scale (exact)
   float mul;          // qco_interval_mul
-  float dc_step[3];   // qco_interval_mul * DC multiplier
+  float dc_step[3];   // qco_interval_mul * DC multiplier over 2^extra_levels
+  const float* dcq[3];  // DcQuantField planes (C.5.2): then the DC step is
+  size_t dcq_stride;    // qco_interval_mul times each sample's value
   const DeviceTables* __restrict__ tab;
   int vec;            // planes and stride allow 16-byte accesses
 };
@@ -1408,7 +1419,8 @@ __device__ __attribute__((always_inline)) inline void qco_tile(const QcoArgs& a,
   // Clamp.  Outside the LLF corner: +-mul AcMul dqs (the quantization step
   // in the scaled domain).  The corner of each varblock (one thread per
   // varblock and channel): its DC samples from the scaled LLF (b = a^-1 per
-  // axis), clamped to +-mul dc_mul, and back (a per axis).
+  // axis), each clamped to +-mul times its DcQuantField, and back (a per
+  // axis).
 #pragma unroll
   for (int k = 0; k < kRecGPT; ++k) {
     const int g = tid + kRecThreads * k;
@@ -1464,7 +1476,10 @@ __device__ __attribute__((always_inline)) inline void qco_tile(const QcoArgs& a,
           float acc = 0.0f;
 #pragma unroll
           for (int y = 0; y < 4; ++y) acc = fmaf(s_ax[1][sy][j][y], D[y][i], acc);
-          L[j][i] = fminf(fmaxf(acc, -a.dc_step[c]), a.dc_step[c]);
+          float t = a.dc_step[c];
+          if (a.dcq[0] && j < cy && i < cx)
+            t = a.mul * a.dcq[c][size_t(gby0 + byl + j) * a.dcq_stride + gbx0 + bxl + i];
+          L[j][i] = fminf(fmaxf(acc, -t), t);
         }
       // back: Ay D' Ax^T
 #pragma unroll
@@ -2851,6 +2866,8 @@ struct DeviceGuard {
   }
 };
 
+int blocks_of(uint32_t v) { return int((v + 7) / 8); }
+
 jxlr_status check_params(const jxlr_frame_params* p) {
   if (!p) return JXLR_E_NULL;
   if (p->xsize == 0 || p->ysize == 0 || p->xsize > JXLR_MAX_DIM || p->ysize > JXLR_MAX_DIM)
@@ -2866,11 +2883,8 @@ jxlr_status check_params(const jxlr_frame_params* p) {
   if (p->out_format < JXLR_OUT_F32 || p->out_format > JXLR_OUT_U16_SRGB) return JXLR_E_PARAM;
   if (p->idct_split < 0 || p->idct_split > 1) return JXLR_E_PARAM;
   if (p->dc_smoothing < 0 || p->dc_smoothing > 1) return JXLR_E_PARAM;
-  const bool el0 = p->extra_levels[0] == 0 && p->extra_levels[1] == 0 && p->extra_levels[2] == 0;
-  if (p->dc_smoothing && !el0) return JXLR_E_PARAM;
   if (p->qco < 0 || p->qco > 1) return JXLR_E_PARAM;
-  if (p->ac_prediction < 0 || p->ac_prediction > 1 || (p->ac_prediction && !el0))
-    return JXLR_E_PARAM;
+  if (p->ac_prediction < 0 || p->ac_prediction > 1) return JXLR_E_PARAM;
   if (p->noise < 0 || p->noise > 1) return JXLR_E_PARAM;
   if (p->num_patches < 0 || p->num_dots < 0) return JXLR_E_PARAM;
   if (p->num_splines < 0 || p->num_spline_points < 0 || p->num_spline_points > (1 << 22) ||
@@ -2880,12 +2894,31 @@ jxlr_status check_params(const jxlr_frame_params* p) {
     if (!std::isfinite(p->dot_colour_quant[c])) return JXLR_E_PARAM;
   for (int i = 0; i < 16; ++i)
     if (!std::isfinite(p->noise_lut[i])) return JXLR_E_PARAM;
-  if (p->qco && (!el0 || !(p->qco_interval_mul >= 0.0f) || !std::isfinite(p->qco_interval_mul)))
-    return JXLR_E_PARAM;
+  if (p->qco && !(p->qco_interval_mul >= 0.0f)) return JXLR_E_PARAM;
+  // every real-valued field must be finite: a NaN passes the range tests
+  // above and would then be dropped or kept inconsistently by the kernels
+  const float* fin[] = {p->dc_mul, &p->kx_dc, &p->kb_dc, p->gab_w1, p->gab_w2,
+                        &p->epf_weight_min, p->epf_scale, p->epf_sharp_lut, &p->epf_range_max,
+                        &p->epf_range_mul, &p->epf_quant_mul, p->opsin_inv, p->opsin_bias,
+                        &p->qco_interval_mul};
+  const int nfin[] = {3, 1, 1, 3, 3, 1, 3, 8, 1, 1, 1, 9, 3, 1};
+  for (size_t k = 0; k < sizeof(nfin) / sizeof(nfin[0]); ++k)
+    for (int i = 0; i < nfin[k]; ++i)
+      if (!std::isfinite(fin[k][i])) return JXLR_E_PARAM;
   return JXLR_OK;
 }
 
-int blocks_of(uint32_t v) { return int((v + 7) / 8); }
+// The DcQuantField planes of io: none, or all three with a stride of at
+// least Wb.
+jxlr_status check_dc_quant(const jxlr_frame_params* p, const jxlr_frame_io* io) {
+  const int set = (io->dc_quant[0] != nullptr) + (io->dc_quant[1] != nullptr) +
+                  (io->dc_quant[2] != nullptr);
+  if (set == 0) return JXLR_OK;
+  if (set != 3) return JXLR_E_NULL;
+  if (io->dc_quant_stride < size_t(blocks_of(p->xsize))) return JXLR_E_SIZE;
+  return JXLR_OK;
+}
+
 
 jxlr_status check_maps_io(const jxlr_frame_params* p, const jxlr_frame_io* io, bool need_sharp) {
   if (!io || !io->strategy || !io->qf_minus_1 || (need_sharp && !io->sharpness))
@@ -2959,15 +2992,53 @@ jxlr_status jxlr_params_default(jxlr_frame_params* p, uint32_t xsize, uint32_t y
   return JXLR_OK;
 }
 
-jxlr_status jxlr_create(jxlr_ctx** out, int device) {
+static_assert(sizeof(jxlr_dequant_encoding) == sizeof(jxlr::DequantEncoding) &&
+                  offsetof(jxlr_dequant_encoding, dist_bands) ==
+                      offsetof(jxlr::DequantEncoding, dist_bands) &&
+                  offsetof(jxlr_dequant_encoding, ecc_bands) ==
+                      offsetof(jxlr::DequantEncoding, ecc_bands) &&
+                  offsetof(jxlr_dequant_encoding, params) == offsetof(jxlr::DequantEncoding, params) &&
+                  offsetof(jxlr_dequant_encoding, afv_weights) ==
+                      offsetof(jxlr::DequantEncoding, afv_weights),
+              "public and table-builder encoding layouts");
+
+jxlr_status jxlr_cfl_from_u8(const uint8_t* x_factor, const uint8_t* b_factor, size_t n,
+                             float* kx, float* kb) {
+  if ((x_factor == nullptr) != (kx == nullptr) || (b_factor == nullptr) != (kb == nullptr))
+    return JXLR_E_NULL;
+  // Annex G; both are exact in binary32 for every byte
+  for (size_t i = 0; kx && i < n; ++i) kx[i] = (float(x_factor[i]) - 128.0f) / 256.0f;
+  for (size_t i = 0; kb && i < n; ++i)
+    kb[i] = float(0.935669 + (double(b_factor[i]) - 128.0) / 128.0);
+  return JXLR_OK;
+}
+
+jxlr_status jxlr_dc_mul_from_header(const float* weights, uint32_t global_scale, uint32_t quant_dc,
+                                    float dc_mul[3]) {
+  if (!dc_mul) return JXLR_E_NULL;
+  if (global_scale < 1 || global_scale > 65536 || quant_dc < 1) return JXLR_E_PARAM;
+  const double def[3] = {4096.0, 512.0, 256.0};
+  for (int c = 0; c < 3; ++c) {
+    const double w = weights ? double(weights[c]) : def[c];
+    if (!(w > 0.0) || !std::isfinite(w)) return JXLR_E_PARAM;
+    dc_mul[c] = float(w / (double(global_scale) * double(quant_dc)));
+  }
+  return JXLR_OK;
+}
+
+jxlr_status jxlr_create(jxlr_ctx** out, int device, const jxlr_dequant_encoding* dq) {
   if (!out) return JXLR_E_NULL;
   *out = nullptr;
-  DeviceGuard g(device);
-  if (!g.ok) return JXLR_E_HIP;
+  // the tables (and the encodings' validity) first, before any device call
   auto* host = new DeviceTables;
-  if (!jxlr::build_tables(host)) {
+  if (!jxlr::build_tables(host, reinterpret_cast<const jxlr::DequantEncoding*>(dq))) {
     delete host;
     return JXLR_E_DEQUANT;
+  }
+  DeviceGuard g(device);
+  if (!g.ok) {
+    delete host;
+    return JXLR_E_HIP;
   }
   auto* ctx = new jxlr_ctx{device, nullptr, nullptr};
   hipError_t e = hipMalloc(&ctx->tables, sizeof(DeviceTables));
@@ -3126,6 +3197,9 @@ jxlr_status make_recon_args(jxlr_ctx* ctx, const jxlr_frame_params* p, const jxl
   a.tab = ctx->tables;
   a.split = p->idct_split;
   a.dc_smooth = p->dc_smoothing;
+  if ((st = check_dc_quant(p, io))) return st;
+  for (int c = 0; c < 3; ++c) a.dcq[c] = p->dc_smoothing ? io->dc_quant[c] : nullptr;
+  a.dcq_stride = io->dc_quant_stride;
   a.pred = nullptr;
   if (p->ac_prediction) {
     if (!io->ac_pred) return JXLR_E_NULL;
@@ -3291,16 +3365,17 @@ jxlr_status jxlr_ac_prediction(jxlr_ctx* ctx, const jxlr_frame_params* p, const 
     if (!io->dc[c]) return JXLR_E_NULL;
   const int Wb = blocks_of(p->xsize), Hb = blocks_of(p->ysize);
   if (io->dc_stride < size_t(Wb)) return JXLR_E_SIZE;
-  // the smoothing window and the cells' DC need the DC multipliers as the
-  // DcQuantField (extra_levels 0)
-  if (p->extra_levels[0] || p->extra_levels[1] || p->extra_levels[2]) return JXLR_E_PARAM;
+  if ((st = check_dc_quant(p, io))) return st;
   PredArgs a{};
   a.Wb = Wb;
   a.Hb = Hb;
   for (int c = 0; c < 3; ++c) {
     a.dc[c] = io->dc[c];
-    a.dc_mul[c] = p->dc_mul[c];
+    a.dc_mul[c] = p->dc_mul[c] / float(1 << p->extra_levels[c]);
+    a.h_mul[c] = p->dc_mul[c];
+    a.dcq[c] = p->dc_smoothing ? io->dc_quant[c] : nullptr;
   }
+  a.dcq_stride = io->dc_quant_stride;
   a.dc_stride = io->dc_stride;
   a.info = info;
   a.kx_dc = p->kx_dc;
@@ -3417,11 +3492,9 @@ jxlr_status jxlr_qco_pass(jxlr_ctx* ctx, const jxlr_frame_params* p, const jxlr_
   if ((st = check_maps_io(p, io, false))) return st;
   if (stride < p->xsize) return JXLR_E_SIZE;
   if (orig == xyb_io) return JXLR_E_PARAM;
-  // the constraint itself is applied here whatever p->qco says; its step
-  // needs the DcQuantField of extra_levels 0 and a usable multiplier
-  if (p->extra_levels[0] || p->extra_levels[1] || p->extra_levels[2] ||
-      !(p->qco_interval_mul >= 0.0f) || !std::isfinite(p->qco_interval_mul))
-    return JXLR_E_PARAM;
+  // the constraint itself is applied here whatever p->qco says
+  if (!(p->qco_interval_mul >= 0.0f)) return JXLR_E_PARAM;
+  if ((st = check_dc_quant(p, io))) return st;
   QcoArgs a{};
   a.W = int(p->xsize);
   a.H = int(p->ysize);
@@ -3435,7 +3508,11 @@ jxlr_status jxlr_qco_pass(jxlr_ctx* ctx, const jxlr_frame_params* p, const jxlr_
   a.stride = stride;
   a.gscale = float(p->global_scale);
   a.mul = p->qco_interval_mul;
-  for (int c = 0; c < 3; ++c) a.dc_step[c] = p->qco_interval_mul * p->dc_mul[c];
+  for (int c = 0; c < 3; ++c) {
+    a.dc_step[c] = p->qco_interval_mul * (p->dc_mul[c] / float(1 << p->extra_levels[c]));
+    a.dcq[c] = io->dc_quant[c];
+  }
+  a.dcq_stride = io->dc_quant_stride;
   a.tab = ctx->tables;
   a.vec = (stride & 3) == 0 && (size_t(p->ysize) * stride & 3) == 0 &&
           (reinterpret_cast<uintptr_t>(orig) & 15) == 0 &&

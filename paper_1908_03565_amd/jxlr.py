@@ -70,7 +70,38 @@ class FrameIO(C.Structure):
         ("spline_offsets", C.c_void_p),
         ("spline_points", C.c_void_p),
         ("spline_dct", C.c_void_p),
+        ("dc_quant", C.c_void_p * 3), ("dc_quant_stride", C.c_size_t),
     ]
+
+
+class DequantEncoding(C.Structure):
+    """jxlr_dequant_encoding (C.6.1)."""
+    _fields_ = [
+        ("mode", C.c_int32), ("copy_from", C.c_int32),
+        ("num_bands", C.c_int32), ("num_ecc_bands", C.c_int32),
+        ("dist_bands", (C.c_double * 17) * 3),
+        ("ecc_bands", (C.c_double * 8) * 3),
+        ("params", (C.c_double * 6) * 3),
+        ("afv_weights", (C.c_double * 8) * 3),
+    ]
+
+
+def dequant_encodings(encs):
+    """A jxlr_dequant_encoding array from 15 dicts (mode, copy_from,
+    num_bands, num_ecc_bands, dist_bands, ecc_bands, params, afv_weights;
+    absent keys 0), indexed by transform type."""
+    if len(encs) != 15:
+        raise ValueError("15 encodings, one per transform type")
+    arr = (DequantEncoding * 15)()
+    for j, e in enumerate(encs):
+        for k in ("mode", "copy_from", "num_bands", "num_ecc_bands"):
+            setattr(arr[j], k, int(e.get(k, 0)))
+        for k in ("dist_bands", "ecc_bands", "params", "afv_weights"):
+            dst = getattr(arr[j], k)
+            for c, row in enumerate(e.get(k, [])):
+                for i, v in enumerate(row):
+                    dst[c][i] = float(v)
+    return arr
 
 
 class BatchPlan(C.Structure):
@@ -126,7 +157,10 @@ _LIB = None
 _SIGS = {
     "jxlr_status_string": ([C.c_int], C.c_char_p),
     "jxlr_params_default": ([C.POINTER(FrameParams), C.c_uint32, C.c_uint32], C.c_int),
-    "jxlr_create": ([C.POINTER(C.c_void_p), C.c_int], C.c_int),
+    "jxlr_create": ([C.POINTER(C.c_void_p), C.c_int, C.c_void_p], C.c_int),
+    "jxlr_cfl_from_u8": ([C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p], C.c_int),
+    "jxlr_dc_mul_from_header": ([C.c_void_p, C.c_uint32, C.c_uint32, C.POINTER(C.c_float)],
+                                C.c_int),
     "jxlr_destroy": ([C.c_void_p], None),
     "jxlr_validate_maps_host": ([C.POINTER(FrameParams), C.c_void_p, C.c_void_p, C.c_void_p,
                                  C.c_size_t], C.c_int),
@@ -237,6 +271,29 @@ def validate_maps_host(p, frame):
                                          st.shape[1])
 
 
+def cfl_from_u8(x_factor=None, b_factor=None):
+    """Annex G: kX, kB (float32 arrays) of u8 XFromY / BFromY values."""
+    xf = None if x_factor is None else np.ascontiguousarray(x_factor, np.uint8)
+    bf = None if b_factor is None else np.ascontiguousarray(b_factor, np.uint8)
+    n = (xf if xf is not None else bf).size
+    kx = None if xf is None else np.empty(xf.shape, np.float32)
+    kb = None if bf is None else np.empty(bf.shape, np.float32)
+    _check(lib().jxlr_cfl_from_u8(None if xf is None else xf.ctypes.data,
+                                  None if bf is None else bf.ctypes.data, n,
+                                  None if kx is None else kx.ctypes.data,
+                                  None if kb is None else kb.ctypes.data), "cfl_from_u8")
+    return kx, kb
+
+
+def dc_mul_from_header(weights=None, global_scale=1, quant_dc=1):
+    """C.4.1 DC multipliers (3 floats)."""
+    w = None if weights is None else np.ascontiguousarray(weights, np.float32)
+    out = (C.c_float * 3)()
+    _check(lib().jxlr_dc_mul_from_header(None if w is None else w.ctypes.data, global_scale,
+                                         quant_dc, out), "dc_mul_from_header")
+    return [float(v) for v in out]
+
+
 def workspace_bytes(p):
     return lib().jxlr_workspace_bytes(C.byref(p))
 
@@ -284,6 +341,9 @@ class DeviceFrame:
                               if self.patch_place is not None else None)
         dt = frame.get("dots")
         self.dots = t(dt, np.int32) if dt is not None and len(dt) else None
+        # C.5.2 DcQuantField, if the frame has one
+        dq = frame.get("dc_quant")
+        self.dc_quant = t(dq, np.float32) if dq is not None else None
         # K.4 splines, if the frame has any
         so = frame.get("spline_offsets")
         has = so is not None and len(so) > 1
@@ -300,6 +360,8 @@ class DeviceFrame:
         c.patch_place = None if self.patch_place is None else self.patch_place.clone()
         c.patch_samples = None if self.patch_samples is None else self.patch_samples.clone()
         c.dots = None if self.dots is None else self.dots.clone()
+        dq = getattr(self, "dc_quant", None)
+        c.dc_quant = None if dq is None else dq.clone()
         for k in ("spline_offsets", "spline_points", "spline_dct"):
             v = getattr(self, k, None)
             setattr(c, k, None if v is None else v.clone())
@@ -315,6 +377,10 @@ class DeviceFrame:
             io.patch_samples_count = self.patch_samples.numel()
         if getattr(self, "dots", None) is not None:
             io.dots = self.dots.data_ptr()
+        if getattr(self, "dc_quant", None) is not None:
+            for c in range(3):
+                io.dc_quant[c] = self.dc_quant[c].data_ptr()
+            io.dc_quant_stride = self.dc_quant.shape[2]
         if getattr(self, "spline_offsets", None) is not None:
             io.spline_offsets = self.spline_offsets.data_ptr()
             io.spline_points = self.spline_points.data_ptr()
@@ -344,7 +410,9 @@ _OUT_DTYPE = {JXLR_OUT_F32: "float32", JXLR_OUT_U8_SRGB: "uint8", JXLR_OUT_U16_S
 class Context:
     """A jxlr context on one HIP device."""
 
-    def __init__(self, device=0):
+    def __init__(self, device=0, dq_enc=None):
+        """dq_enc: None (the C.6.1.1 defaults) or 15 encoding dicts, one per
+        transform type (see dequant_encodings)."""
         import torch
         # torch's HIP runtime is initialised first: the buffers and streams
         # this binding hands to the library are torch's, and a runtime that
@@ -352,7 +420,9 @@ class Context:
         torch.cuda.init()
         self.device = device
         h = C.c_void_p()
-        _check(lib().jxlr_create(C.byref(h), int(device)), "create")
+        enc = None if dq_enc is None else dequant_encodings(dq_enc)
+        _check(lib().jxlr_create(C.byref(h), int(device), None if enc is None else C.cast(enc, C.c_void_p)),
+               "create")
         self.handle = h
 
     def close(self):

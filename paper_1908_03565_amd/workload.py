@@ -195,6 +195,119 @@ def frame(W, H, seed, choices=None, p_dct32=None, qf_const=None, cfl_zero=False,
                 out_format=out_format)
 
 
+# C.6.1 encoding modes and the mode each transform type's default encoding
+# (C.6.1.1) is written in.
+DQ_LIBRARY, DQ_IDENTITY, DQ_DCT2, DQ_DCT4, DQ_DCT4X8, DQ_AFV, DQ_DCT, DQ_COPY = range(8)
+DEFAULT_MODE = {0: DQ_DCT, 1: DQ_IDENTITY, 2: DQ_DCT2, 3: DQ_DCT4, 4: DQ_DCT, 5: DQ_DCT,
+                6: DQ_DCT, 7: DQ_DCT, 8: DQ_DCT, 9: DQ_DCT, 10: DQ_DCT, 11: DQ_DCT,
+                12: DQ_DCT4X8, 13: DQ_DCT4X8, 14: DQ_AFV}
+
+
+def _is64(s):
+    return BLOCKS[s] == (1, 1)
+
+
+# Weight scale per transform type and channel for synthetic encodings:
+# about the first distance band of the type's default encoding (C.6.1.1),
+# and for the types whose numerators are 1 (Identity, DCT2, AFV) about the
+# bulk of Identity's default weights.  Every mode's parameters for type s
+# are drawn around WEIGHT_SCALE[s], so that the decoded samples stay in the
+# range the default matrices give.
+WEIGHT_SCALE = {0: (5.0, 1.1, 1.0), 1: (220.0, 30.0, 9.0), 2: (220.0, 30.0, 9.0),
+                3: (32.0, 6.0, 4.0), 4: (3.2, 0.78, 0.22), 5: (0.48, 0.22, 0.12),
+                6: (5.0, 1.0, 0.35), 7: (5.0, 1.0, 0.35), 8: (0.9, 0.36, 0.25),
+                9: (0.9, 0.36, 0.25), 10: (1.13, 0.39, 0.1), 11: (1.13, 0.39, 0.1),
+                12: (17.0, 4.6, 0.8), 13: (17.0, 4.6, 0.8), 14: (220.0, 30.0, 9.0)}
+
+
+def _bands(rng, scale, nmax=17):
+    """Random distance and eccentricity bands: the first distance band of
+    each channel is the type's weight scale times U[0.5, 2]; later bands move
+    it by factors mostly below 1 towards high frequencies, their product
+    between about 1/35 and 2 whatever the band count (the defaults' products
+    span 1/10 to 1/70)."""
+    nb = int(rng.integers(2, nmax + 1))
+    ne = int(rng.integers(1, 9))
+    a = 4.0 / (nb - 1)
+    db = [[b * rng.uniform(0.5, 2.0)] + list(rng.uniform(-a, 0.2 * a, nb - 1)) for b in scale]
+    eb = [list(rng.uniform(-0.3, 0.3, ne) / ne) for _ in range(3)]
+    return dict(num_bands=nb, num_ecc_bands=ne, dist_bands=db, ecc_bands=eb)
+
+
+def dequant_encoding(rng, s, mode, copy_from=0):
+    """One synthetic C.6.1 encoding of mode `mode` for transform type s, its
+    parameters drawn around the type's weight scale in the proportions the
+    draft's defaults of that mode show."""
+    e = {"mode": mode}
+    sc = WEIGHT_SCALE[s]
+    if mode == DQ_COPY:
+        e["copy_from"] = copy_from
+    elif mode == DQ_IDENTITY:
+        e["params"] = [[w, w * rng.uniform(1, 30), w * rng.uniform(1, 20)]
+                       for w in (b * rng.uniform(0.5, 2.0) for b in sc)]
+    elif mode == DQ_DCT2:
+        e["params"] = [list(b * rng.uniform(0.5, 2.0) * np.array([12, 8, 4, 2, 1.5, 1]) *
+                            rng.uniform(0.7, 1.3, 6)) for b in sc]
+    elif mode in (DQ_DCT4, DQ_DCT4X8, DQ_DCT):
+        e.update(_bands(rng, sc))
+        e["params"] = [list(rng.uniform(0.5, 1.5, 2)) for _ in range(3)]
+    elif mode == DQ_AFV:
+        e["afv_weights"] = [list(b * rng.uniform(0.5, 2.0, 4) * np.array([19, 0.7, 1.3, 0.7])) +
+                            [b * rng.uniform(0.5, 2.0)] + list(rng.uniform(-2.5, 0.2, 3)) for b in sc]
+        e["params"] = [list(rng.uniform(0.5, 1.5, 2)) for _ in range(3)]
+    return e
+
+
+def dequant_encodings(seed, modes=None):
+    """Fifteen synthetic C.6.1 encodings (one per transform type, already
+    read from a stream).  Each type draws a mode among `modes` (default all
+    eight) that is valid for its matrix: the 64-entry modes only for the
+    7 types with 64 coefficients, Copy only of an earlier matrix whose
+    encoding (Library resolved to its default mode) suits this one and
+    whose numerators are of the same kind (1 for Identity, DCT2 and AFV,
+    DCT scale factors for the others), so that values stay in range."""
+    rng = np.random.default_rng(seed)
+    modes = list(range(8)) if modes is None else list(modes)
+    unit = (1, 2, 14)
+    encs, resolved = [], []
+
+    def sources(s):
+        return [j for j in range(s) if (_is64(s) or resolved[j] == DQ_DCT)
+                and ((j in unit) == (s in unit))]
+
+    for s in range(15):
+        ok = []
+        for m in modes:
+            if m in (DQ_IDENTITY, DQ_DCT2, DQ_DCT4, DQ_DCT4X8, DQ_AFV) and not _is64(s):
+                continue
+            if m == DQ_COPY and not sources(s):
+                continue
+            ok.append(m)
+        if not ok:
+            ok = [DQ_LIBRARY]
+        m = ok[int(rng.integers(len(ok)))]
+        src = 0
+        if m == DQ_COPY:
+            cand = sources(s)
+            src = cand[int(rng.integers(len(cand)))]
+        encs.append(dequant_encoding(rng, s, m, src))
+        resolved.append(resolved[src] if m == DQ_COPY else DEFAULT_MODE[s] if m == DQ_LIBRARY else m)
+    return encs
+
+
+def dc_quant_field(rng, frame_dict, extra_levels):
+    """A C.5.2 DcQuantField for a frame: per DC sample and channel
+    dc_mul[c] / 2^k, k drawn uniformly in 0..extra_levels[c] (the values the
+    decoded deltas can give), float32 (3, Hb, Wb)."""
+    Hb, Wb = frame_dict["dc"].shape[1:]
+    dc_mul = frame_dict["params"]["dc_mul"]
+    out = np.empty((3, Hb, Wb), np.float32)
+    for c in range(3):
+        k = rng.integers(0, extra_levels[c] + 1, size=(Hb, Wb))
+        out[c] = (np.float32(dc_mul[c]) / (2.0 ** k)).astype(np.float32)
+    return out
+
+
 def c1():
     return frame(256, 256, seed=0, choices=[DCT8], qf_const=8, cfl_zero=True,
                  epf_iters=0, gab=1, name="c1_256x256_dct8")

@@ -12,6 +12,10 @@ int shim_dequant(int s, int c, double* out) { return jxlr::dequant_matrix_f64(s,
 void shim_inverse(int n, double* out) { jxlr::inverse_transform_matrix_f64(n, out); }
 void shim_mul_table(int shift, int32_t* t) { jxlr::epf_mul_table(shift, t); }
 int shim_build() { return jxlr::build_tables(&g_tables) ? 1 : 0; }
+int shim_dequant_enc(int s, int c, const void* enc, double* out) {
+  return jxlr::dequant_matrix_f64(s, c, out, static_cast<const jxlr::DequantEncoding*>(enc)) ? 1 : 0;
+}
+int shim_encoding_size() { return int(sizeof(jxlr::DequantEncoding)); }
 const float* shim_t8() { return g_tables.t8; }
 const float* shim_t16() { return g_tables.t16; }
 const float* shim_t32() { return g_tables.t32; }

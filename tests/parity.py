@@ -157,7 +157,7 @@ def acpred_mask(q, frame, rel=1e-5):
     dq = frame["dc"].astype(np.float64) * np.array(q.dc_mul)[:, None, None]
     dq /= (2.0 ** np.array(list(q.extra_levels)))[:, None, None]
     if q.dc_smoothing:
-        dq = O.dc_smooth(q, dq)
+        dq = O.dc_smooth(q, dq, frame.get("dc_quant"))
     dq[0] += q.kx_dc * dq[1]
     dq[2] += q.kb_dc * dq[1]
     cells, margin = O.ac_prediction_image(q, frame["strategy"], dq, want_margin=True)

@@ -89,25 +89,33 @@ def test_parameter_ranges():
         assert J.validate_maps_host(p, f) == 7, k
         assert J.workspace_bytes(p) == 0
     assert J.validate_maps_host(J.params(0, 8), _frame(8, 8)) == 2
-    # smoothing takes dcq from the DC multipliers, which needs extra_levels 0
-    p = J.params(64, 64, dc_smoothing=1, extra_levels=(0, 1, 0))
-    assert J.validate_maps_host(p, f) == 7
-    assert J.validate_maps_host(J.params(64, 64, dc_smoothing=1), f) == 0
-    # the quantization constraint: a flag, a finite non-negative multiplier,
-    # and the DC step from the multipliers (extra_levels 0)
+    # extra_levels 0..3, with smoothing, the constraint and AC prediction too
+    for el in ((0, 1, 0), (1, 2, 1), (3, 3, 3)):
+        for kw in (dict(dc_smoothing=1), dict(qco=1), dict(ac_prediction=1), {}):
+            assert J.validate_maps_host(J.params(64, 64, extra_levels=el, **kw), f) == 0, (el, kw)
+    for el in ((0, 4, 0), (-1, 0, 0)):
+        assert J.validate_maps_host(J.params(64, 64, extra_levels=el), f) == 7
+    # the quantization constraint: a flag and a finite non-negative multiplier
     for kw in (dict(qco=2), dict(qco=-1), dict(qco=1, qco_interval_mul=-0.25),
-               dict(qco=1, qco_interval_mul=float("nan")), dict(qco=1, qco_interval_mul=float("inf")),
-               dict(qco=1, extra_levels=(1, 0, 0))):
+               dict(qco=1, qco_interval_mul=float("nan")), dict(qco=1, qco_interval_mul=float("inf"))):
         p = J.params(64, 64, **kw)
         assert J.validate_maps_host(p, f) == 7, kw
         assert J.workspace_bytes(p) == 0, kw
     assert J.validate_maps_host(J.params(64, 64, qco=1, qco_interval_mul=0.0), f) == 0
-    # AC prediction: a flag, with the DC multipliers as the DcQuantField
-    for kw in (dict(ac_prediction=2), dict(ac_prediction=1, extra_levels=(0, 0, 2))):
+    assert J.validate_maps_host(J.params(64, 64, ac_prediction=2), f) == 7
+    assert J.params(64, 64).ac_prediction == 0
+    # every real-valued field must be finite (the oracle rejects the same)
+    nan, inf = float("nan"), float("inf")
+    for kw in (dict(epf_scale=(1.0, nan, 1.0)), dict(epf_range_max=inf), dict(epf_range_mul=nan),
+               dict(epf_quant_mul=-inf), dict(dc_mul=(1.0, 1.0, nan)), dict(kx_dc=nan),
+               dict(gab_w1=(0.1, inf, 0.1)), dict(opsin_inv=[1.0] * 8 + [nan]),
+               dict(opsin_bias=(0.0, nan, 0.0)), dict(epf_sharp_lut=[0.0] * 7 + [inf]),
+               dict(epf_weight_min=nan)):
         p = J.params(64, 64, **kw)
         assert J.validate_maps_host(p, f) == 7, kw
-        assert J.workspace_bytes(p) == 0, kw
-    assert J.params(64, 64).ac_prediction == 0
+        q = O.params(64, 64, **kw)
+        with pytest.raises(O.OracleError):
+            O.reconstruct(q, dict(wl.small(64, 64, seed=1), params={}))
     # noise: a flag and a finite LUT
     lut = np.zeros(16)
     lut[3] = float("nan")
@@ -221,6 +229,59 @@ def test_dequant_tables_match_oracle(shim):
             np.testing.assert_allclose(buf[1:], ref[1:], rtol=1e-12, err_msg=f"{s},{c}")
             f32 = _arr(shim.shim_dq(), DQ_FLOATS)[shim.shim_dq_offset(s) + c * bx * by:][:bx * by]
             np.testing.assert_allclose(f32[1:], ref[1:], rtol=1e-7)
+
+
+def test_encoded_dequant_tables_match_oracle(shim):
+    # random encodings of every mode (the two sides build them independently)
+    assert shim.shim_encoding_size() == C.sizeof(J.DequantEncoding)
+    for seed in range(12):
+        encs = wl.dequant_encodings(seed)
+        arr = J.dequant_encodings(encs)
+        for s in range(15):
+            bx, by = O.varblock_size(s)
+            for c in range(3):
+                buf = np.zeros(bx * by)
+                assert shim.shim_dequant_enc(s, c, C.cast(arr, C.c_void_p),
+                                             buf.ctypes.data_as(C.POINTER(C.c_double))) == 1
+                ref = O.dequant_matrix(s, c, encs).ravel()
+                np.testing.assert_allclose(buf[1:], ref[1:], rtol=1e-12, err_msg=f"{seed},{s},{c}")
+    # ill-formed encodings are rejected by both
+    bad = [{"mode": 0}] * 15
+    for s, e in ((4, {"mode": 1, "params": [[1.0] * 3] * 3}), (3, {"mode": 7, "copy_from": 3}),
+                 (0, {"mode": 9}), (5, {"mode": 6, "num_bands": 1, "num_ecc_bands": 1,
+                                        "dist_bands": [[1.0]] * 3, "ecc_bands": [[0.0]] * 3}),
+                 (0, {"mode": 6, "num_bands": 2, "num_ecc_bands": 1,
+                      "dist_bands": [[-1.0, 0.0]] * 3, "ecc_bands": [[0.0]] * 3})):
+        encs = list(bad)
+        encs[s] = e
+        arr = J.dequant_encodings(encs)
+        buf = np.zeros(1024)
+        assert shim.shim_dequant_enc(s, 0, C.cast(arr, C.c_void_p),
+                                     buf.ctypes.data_as(C.POINTER(C.c_double))) == 0, e
+        with pytest.raises(O.OracleError):
+            O.dequant_matrix(s, 0, encs)
+
+
+def test_cfl_and_dc_multiplier_helpers():
+    # Annex G on every byte value, exact in binary32
+    v = np.arange(256, dtype=np.uint8)
+    kx, kb = J.cfl_from_u8(v, v)
+    np.testing.assert_array_equal(kx, ((v.astype(np.float64) - 128) / 256).astype(np.float32))
+    np.testing.assert_array_equal(kb, (0.935669 + (v.astype(np.float64) - 128) / 128).astype(np.float32))
+    assert kx[128] == 0.0 and kb[128] == np.float32(0.935669)
+    kx, kb = J.cfl_from_u8(x_factor=v)
+    assert kb is None and kx[0] == -0.5
+    # C.4.1: defaults {4096, 512, 256} over global_scale * quant_dc
+    np.testing.assert_allclose(J.dc_mul_from_header(None, 1, 1), [4096, 512, 256])
+    np.testing.assert_allclose(J.dc_mul_from_header(None, 8192, 16), [4096 / 131072, 512 / 131072,
+                                                                       256 / 131072], rtol=1e-7)
+    np.testing.assert_allclose(J.dc_mul_from_header([3.0, 5.0, 7.0], 2, 3), [0.5, 5 / 6, 7 / 6],
+                               rtol=1e-7)
+    assert J.params(8, 8).dc_mul[0] == J.dc_mul_from_header()[0]
+    for args in (([1.0, 0.0, 1.0], 1, 1), (None, 0, 1), (None, 1, 0), (None, 65537, 1),
+                 ([1.0, float("nan"), 1.0], 1, 1)):
+        with pytest.raises(J.JxlrError):
+            J.dc_mul_from_header(*args)
 
 
 def test_afv_basis_matches_oracle(shim):

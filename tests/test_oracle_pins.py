@@ -1489,6 +1489,64 @@ def test_jpeg1_component_is_the_orthonormal_idct_of_the_dequantized_block():
     assert np.ptp(p1, axis=0).max() < 1e-12 and np.ptp(p1[0]) > 1.0
 
 
+def _gab_kernel(w1, w2):
+    k = np.array([[w2, w1, w2], [w1, 1.0, w1], [w2, w1, w2]])
+    return k / k.sum()
+
+
+def test_jpeg1_gaborish_smoothing_is_the_reflecting_j4_correlation():
+    # with a limit above the 36 interior pixels every block takes the
+    # smoothed plane: the 3x3 kernel {1, w1, w2} normalized (J.4, the bytes
+    # over 1024), mirrored at the plane's edges like scipy's "reflect"
+    rng = _rng(41)
+    pix = rng.uniform(-100, 100, size=(24, 40))
+    code = (118, 63, 40, 255)
+    out = O.jpeg1_gaborish(pix, code)
+    ref = ndi.correlate(pix, _gab_kernel(118 / 1024, 63 / 1024), mode="reflect")
+    np.testing.assert_allclose(out, ref, rtol=0, atol=1e-12)
+    # limit 0: no block has fewer than 0 differing pixels, nothing changes
+    np.testing.assert_array_equal(O.jpeg1_gaborish(pix, (118, 63, 40, 0)), pix)
+
+
+def test_jpeg1_gaborish_counts_only_the_block_interior():
+    # blocks of constant value with steps between them: the smoothing moves
+    # only the pixels next to a block edge (offsets 0 and 7), which the
+    # count leaves out, so with limit 1 every block is smoothed
+    vals = np.array([[0.0, 50.0, -30.0], [80.0, 10.0, 20.0]])
+    pix = np.kron(vals, np.ones((8, 8)))
+    sm = ndi.correlate(pix, _gab_kernel(118 / 1024, 63 / 1024), mode="reflect")
+    assert np.abs(sm - pix).max() > 5.0
+    inner = np.zeros_like(pix, bool)
+    for by in range(2):
+        for bx in range(3):
+            inner[8 * by + 1:8 * by + 7, 8 * bx + 1:8 * bx + 7] = True
+    assert np.abs(sm - pix)[inner].max() < 1e-12
+    np.testing.assert_allclose(O.jpeg1_gaborish(pix, (118, 63, 16, 1)), sm, atol=1e-12)
+
+
+def test_jpeg1_gaborish_gate_brute_force():
+    # random planes and codes against a direct count per block
+    rng = _rng(42)
+    for trial in range(12):
+        hib, wib = int(rng.integers(1, 4)), int(rng.integers(1, 5))
+        pix = rng.normal(0, 10, size=(8 * hib, 8 * wib))
+        # some blocks get a strong pattern (many large differences)
+        for by in range(hib):
+            for bx in range(wib):
+                if rng.random() < 0.5:
+                    pix[8 * by:8 * by + 8, 8 * bx:8 * bx + 8] += 60 * (np.indices((8, 8)).sum(0) % 2)
+        code = tuple(int(v) for v in (rng.integers(0, 256), rng.integers(0, 256),
+                                      rng.integers(0, 256), rng.integers(0, 40)))
+        sm = ndi.correlate(pix, _gab_kernel(code[0] / 1024, code[1] / 1024), mode="reflect")
+        want = pix.copy()
+        for by in range(hib):
+            for bx in range(wib):
+                d = np.abs(pix - sm)[8 * by + 1:8 * by + 7, 8 * bx + 1:8 * bx + 7]
+                if (d > code[2] / 16).sum() < code[3]:
+                    want[8 * by:8 * by + 8, 8 * bx:8 * bx + 8] = sm[8 * by:8 * by + 8, 8 * bx:8 * bx + 8]
+        np.testing.assert_allclose(O.jpeg1_gaborish(pix, code), want, atol=1e-12)
+
+
 def test_jpeg1_colour_transform_inverts_the_jfif_forward_matrix():
     # the printed constants are the JFIF forward transform's inverse to five digits
     fwd = np.array([[0.299, 0.587, 0.114], [-0.168736, -0.331264, 0.5], [0.5, -0.418688, -0.081312]])
