@@ -1,19 +1,21 @@
 """Benchmark: decoded megapixels per second, coefficients -> RGB, on one GPU.
 
-Default workload (c2): one 2048x2048 frame, DctSelect drawn per 32x32 region
-from ten transform types, quant field U{1..32}, chroma-from-luma U[-1, 1] per
-64x64 tile, two edge-preserving filter passes, Gaborish, binary32 linear RGB
-out (synthetic inputs, seeded).  A step is one whole reconstruction of the
-frame with its inputs already resident in device memory: block info +
-reconstruct, two EPF passes, Gaborish + XYB -> RGB.  The steps call the same
-stage entry points as jxlr_decode, with HIP events recorded between them on
-the launch stream, so that each kernel's duration is measured inside the
-timed region.
+Default workload (c4, the largest single-GPU configuration): a batch of 64
+frames, sides log-uniform in [256, 3072] rounded to 8 (89.7 MP in all),
+DctSelect drawn per 32x32 region from ten transform types, quant field
+U{1..32}, chroma-from-luma U[-1, 1] per 64x64 tile, one edge-preserving
+filter pass, Gaborish, 8-bit sRGB out (synthetic inputs, seeded).  A step is
+one replay of the captured HIP graph of the whole batch (persistent stage
+kernels with the autotuned schedule) with its inputs already resident in
+device memory; a second timed loop runs the same batch stage by stage with
+HIP events between the stages for the per-kernel durations.  --workload
+c1x1024 is the same for 1024 copies of the 256x256 DCT8 frame.
 
-Batch workloads (--workload c4 | c1x1024): a step is one replay of the
-captured HIP graph of the whole batch (persistent stage kernels with the
-autotuned schedule); a second timed loop runs the same batch stage by stage
-with events between the stages for the per-kernel durations.
+Single-frame workloads (--workload c1 | c2 | c2t | c3): a step is one whole
+reconstruction of the frame: block info + reconstruct, the EPF passes,
+Gaborish + XYB -> RGB.  The steps call the same stage entry points as
+jxlr_decode, with HIP events recorded between them on the launch stream, so
+that each kernel's duration is measured inside the timed region.
 
 After timing, the output is compared with the FP64 oracle (full frame for
 c1/c2/c3; a sample of frames for the batches), and the oracle's wall time on
@@ -368,7 +370,7 @@ def bench_frame(args, J, wl, torch, np):
                    "splines": args.splines,
                    "gaborish": bool(p.gab), "output": "f32 linear RGB / 255",
                    "frames_per_step": 1,
-                   "idct": "split bf16 hi+lo on matrix cores, f32 accumulate" if args.split
+                   "idct": "split f16 hi+lo on matrix cores (block-scaled), f32 accumulate" if args.split
                    else "f32"},
         "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 5),
                        "p99": round(float(np.percentile(lat, 99)), 5)},
@@ -546,7 +548,7 @@ def bench_batch(args, J, wl, torch, np):
         "config": {"workload": name, "frames_per_step": len(ps), "megapixels_per_step": round(mp, 4),
                    "tiles": plan.total_tiles, "epf_iters": n_epf, "output": out_name,
                    "schedule": cfg.as_dict(), "hip_graph": True,
-                   "idct": "split bf16 hi+lo on matrix cores, f32 accumulate" if args.split
+                   "idct": "split f16 hi+lo on matrix cores (block-scaled), f32 accumulate" if args.split
                    else "f32"},
         "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 5),
                        "p99": round(float(np.percentile(lat, 99)), 5)},
@@ -655,7 +657,7 @@ def bench_serving(args, J, wl, torch, np):
                    "seconds": args.c5_seconds, "requests": summ["requests"],
                    "megapixels": summ["megapixels"], "budget_gib": args.c5_budget_gb,
                    "output": "70% u8 / 30% u16 sRGB", "epf_iters": "U{0..3}",
-                   "idct": "split bf16 hi+lo on matrix cores, f32 accumulate" if args.split
+                   "idct": "split f16 hi+lo on matrix cores (block-scaled), f32 accumulate" if args.split
                    else "f32"},
         "latency_ms": summ["latency_ms"],
         "serving": summ,
@@ -754,7 +756,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="c2",
+    # default: the 64-frame batch, the largest single-GPU configuration
+    ap.add_argument("--workload", default="c4",
                     choices=["c1", "c2", "c2t", "c3", "c4", "c1x1024", "c5", "j1"])
     ap.add_argument("--no-check", action="store_true", help="skip the oracle comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")

@@ -26,7 +26,8 @@
  * On any error no output content is guaranteed.
  *
  * Threading: a context may be used from several host threads and streams at
- * once, provided each concurrent call has its own workspace and outputs.
+ * once, provided each concurrent call has its own workspace and outputs; the
+ * sticky device-validation flag is one per context (jxlr_get_device_status).
  */
 #ifndef JXLR_H
 #define JXLR_H
@@ -422,10 +423,11 @@ jxlr_status jxlr_finish(jxlr_ctx* ctx, const jxlr_frame_params* p, const jxlr_fr
 /* ---- JPEG1 direct rasterization (M.6) ----------------------------------------
  * A recompressed JPEG1 frame (M.4 already decoded: quantized DCT coefficients
  * per component and the quantization tables) straight to RGB: dequantization
- * (M.6.1) and IDCT (M.6.2) per component, 2x linear upsampling of subsampled
- * components (M.6.4), YCbCr -> RGB (M.6.5) and the crop (M.6.6).  Not done:
- * the optional side channels (coefficient conditioning M.6.1.1, gated
- * Gaborish M.6.3, HDR colour spaces M.6.5.1).  Errors, all synchronous and
+ * (M.6.1) and IDCT (M.6.2) per component, the gated Gaborish of the M.6.3
+ * side channel when present, 2x linear upsampling of subsampled components
+ * (M.6.4), YCbCr -> RGB (M.6.5) and the crop (M.6.6).  Not done: the other
+ * optional side channels (coefficient conditioning M.6.1.1, HDR colour
+ * spaces M.6.5.1).  Errors, all synchronous and
  * before any launch: JXLR_E_NULL for a missing pointer; JXLR_E_PARAM for a
  * component count other than 1 or 3, a sampling factor outside {1, 2} or
  * above component 0's, a quantization step outside 1..65535 or a component
@@ -438,15 +440,32 @@ typedef struct {
   int32_t num_components;     /* 1 (grey) or 3 (Y, Cb, Cr) */
   int32_t h_samp[3], v_samp[3]; /* sampling factors 1 or 2; component 0 the largest */
   int32_t quant[3][64];       /* quantization steps 1..65535, index 8 u + v */
+  /* M.6.3 side channel ("BRN:GAB"): 1 if present, applied after the IDCT of
+   * every component; gab_code[c] holds the component's four decoded bytes:
+   * gab_weight1 * 1024, gab_weight2 * 1024, threshold * 16, limit. */
+  int32_t gab;
+  uint8_t gab_code[3][4];
 } jxlr_jpeg1_params;
 
 /* Blocks of component c: whole MCUs of 8 h_samp[0] x 8 v_samp[0] pixels
  * cover the image, and component c has h_samp[c] x v_samp[c] blocks per MCU. */
 jxlr_status jxlr_jpeg1_blocks(const jxlr_jpeg1_params* p, int32_t c, int32_t* wib, int32_t* hib);
 
-/* Device workspace of jxlr_jpeg1_decode: one float plane per component
- * (0 if p is invalid). */
+/* Device workspace of jxlr_jpeg1_decode: one float plane per component, two
+ * with the M.6.3 side channel (0 if p is invalid). */
 size_t jxlr_jpeg1_workspace_bytes(const jxlr_jpeg1_params* p);
+
+/* M.6.3 for component c with its side-channel bytes p->gab_code[c]
+ * (whatever p->gab says): the J.4 smoothing of pix_in (3x3 kernel, centre 1,
+ * edge gab_weight1, diagonal gab_weight2, normalized; mirrored at the
+ * plane's edges), then per 8x8 block the smoothed values when fewer than
+ * limit of the block's 6x6 interior pixels (offsets 1..6) differ from them
+ * by more than the threshold, else the block's own, into pix_out.  Planes
+ * as jxlr_jpeg1_idct writes them (float [8 hib][8 wib], strides multiples
+ * of 4, pointers 16-byte aligned), distinct (JXLR_E_PARAM otherwise). */
+jxlr_status jxlr_jpeg1_gaborish(jxlr_ctx* ctx, const jxlr_jpeg1_params* p, int32_t c,
+                                const float* pix_in, size_t in_stride, float* pix_out,
+                                size_t out_stride, hipStream_t stream);
 
 /* M.6.1-M.6.2 for component c: coef int32 [8 hib][8 wib] device memory, row
  * stride coef_stride elements, coefficient 8 u + v of block (bx, by) at row
@@ -469,7 +488,8 @@ jxlr_status jxlr_jpeg1_color(jxlr_ctx* ctx, const jxlr_jpeg1_params* p, const fl
                              const size_t pix_stride[3], float* const rgb[3], size_t rgb_stride,
                              hipStream_t stream);
 
-/* The whole rasterization: jxlr_jpeg1_idct of every component into ws, then
+/* The whole rasterization: jxlr_jpeg1_idct of every component into ws, with
+ * p->gab jxlr_jpeg1_gaborish of each into the second half of ws, then
  * jxlr_jpeg1_color.  coef / coef_stride as for jxlr_jpeg1_idct, per
  * component (entries past num_components ignored). */
 jxlr_status jxlr_jpeg1_decode(jxlr_ctx* ctx, const jxlr_jpeg1_params* p,
@@ -498,6 +518,7 @@ typedef struct jxlr_batch_plan {
   int total_regions; /* 32x32 DctSelect regions over all frames */
   int max_epf_iters;
   size_t frames_offset, tile_frame_offset, tile_start_offset, region_start_offset;
+  int any_split;     /* some frame has idct_split set */
 } jxlr_batch_plan;
 
 /* Schedule of the four persistent stage kernels.  grid_*: workgroup count;
@@ -521,12 +542,15 @@ enum { JXLR_STAGE_INFO = 0, JXLR_STAGE_RECON = 1, JXLR_STAGE_EPF = 2, JXLR_STAGE
 
 /* Validates every frame as the single-frame entry points do and writes the
  * batch descriptors into `ws` (device memory, ws_bytes >=
- * jxlr_batch_workspace_bytes(n, p)) with a synchronous copy.  p[i] and io[i]
- * are host arrays of n entries; the device buffers io[i] names must stay
- * valid while the plan is run.  Calls no kernel. */
+ * jxlr_batch_workspace_bytes(n, p)).  The copies are ordered on `stream`
+ * (after any earlier work on it, such as a previous batch still reading the
+ * same workspace) and the call waits for them, so it synchronizes `stream`;
+ * a workspace reused on another stream must be free of that stream's work
+ * first.  p[i] and io[i] are host arrays of n entries; the device buffers
+ * io[i] names must stay valid while the plan is run.  Calls no kernel. */
 jxlr_status jxlr_batch_prepare(jxlr_ctx* ctx, int n, const jxlr_frame_params* p,
                                const jxlr_frame_io* io, void* ws, size_t ws_bytes,
-                               jxlr_batch_plan* plan);
+                               jxlr_batch_plan* plan, hipStream_t stream);
 
 /* Enqueues the whole path for every frame of the plan on `stream`: block
  * info, reconstruction, max_epf_iters EPF passes (a frame with fewer passes
@@ -552,7 +576,8 @@ jxlr_status jxlr_batch_stage(jxlr_ctx* ctx, const jxlr_batch_plan* plan, int sta
 jxlr_status jxlr_autotune(jxlr_ctx* ctx, const jxlr_batch_plan* plan, int reps,
                           jxlr_launch_config* best, float* best_ms, hipStream_t stream);
 
-/* jxlr_batch_prepare followed by jxlr_batch_run with the default config. */
+/* jxlr_batch_prepare (on `stream`) followed by jxlr_batch_run with the
+ * default config. */
 jxlr_status jxlr_decode_batch(jxlr_ctx* ctx, int n, const jxlr_frame_params* p,
                               const jxlr_frame_io* io, void* ws, size_t ws_bytes,
                               hipStream_t stream);
@@ -567,8 +592,14 @@ jxlr_status jxlr_graph_create(jxlr_ctx* ctx, const jxlr_batch_plan* plan,
 jxlr_status jxlr_graph_launch(jxlr_graph* g, hipStream_t stream);
 void jxlr_graph_destroy(jxlr_graph* g);
 
-/* Reads and clears the sticky device-validation flag: JXLR_OK or
- * JXLR_E_DEVICE_VALIDATION.  Synchronizes `stream`. */
+/* Reads and clears (in one atomic exchange on the device, ordered on
+ * `stream`) the sticky device-validation flag: JXLR_OK or
+ * JXLR_E_DEVICE_VALIDATION.  Synchronizes `stream`.  The flag belongs to the
+ * context: every call on the context sets the same flag, whatever its
+ * stream, so with calls in flight on several streams a set flag does not
+ * say which call set it.  Callers that need the flag per request use a
+ * context per stream, or check the maps on the host first
+ * (jxlr_validate_maps_host). */
 jxlr_status jxlr_get_device_status(jxlr_ctx* ctx, hipStream_t stream);
 
 #ifdef __cplusplus

@@ -37,7 +37,7 @@ using jxlr::kSrgbBucketsPadded;
 struct jxlr_ctx {
   int device;
   DeviceTables* tables;  // device memory
-  int* status;           // device memory, sticky validation flag
+  int* status;           // device memory: [0] the sticky validation flag, [1] its last read
 };
 
 namespace {
@@ -293,10 +293,12 @@ __device__ __attribute__((always_inline)) inline void block_dc(
       const int32_t* p2 = dc[c] + d + dc_stride;
       const float e = float(p0[0]) + float(p1[-1]) + float(p1[1]) + float(p2[0]);
       const float g = float(p0[-1]) + float(p0[1]) + float(p2[-1]) + float(p2[1]);
-      const float sv = *v[c];
-      const float q = dcq[0] ? dcq[c][size_t(by) * dcq_stride + bx] : dc_mul[c];
+      // the neighbours dequantized with the multiplier, the window from the
+      // sample's dequantization range
+      const float sv = *v[c], m = dc_mul[c];
+      const float q = dcq[0] ? dcq[c][size_t(by) * dcq_stride + bx] : m;
       const float wa = fmaf(0.05226273532324128f, sv,
-                            q * fmaf(0.20345139757231578f, e, 0.0334829185968739f * g));
+                            m * fmaf(0.20345139757231578f, e, 0.0334829185968739f * g));
       if (sv - 0.5f * q <= wa && wa <= sv + 0.5f * q) *v[c] = wa;
     }
   }
@@ -432,41 +434,59 @@ __device__ inline int dq_off_lut(int s) {
 // A 32x32 region tiled by varblocks of one DCT type is transformed as two
 // matrix products, columns Y = A_col K and rows S = Y A_row^T, with A the
 // block-diagonal plain DCT-III matrix of the varblock height / width.  Each
-// product runs on v_mfma_f32_32x32x16_bf16: both operands are split into a
-// bfloat16 high part and a bfloat16 rest, and hi*hi + hi*lo + lo*hi is
-// accumulated in binary32 (the dropped lo*lo term is below 2^-16 of each
-// product).  Operand layouts of the instruction (one wave): lane l supplies
-// A[l mod 32][8 (l / 32) + e] and B[8 (l / 32) + e][l mod 32], e < 8, and
-// accumulator q of lane l is C[8 (q / 4) + 4 (l / 32) + q mod 4][l mod 32].
+// product runs on v_mfma_f32_32x32x16_f16: both operands are split into a
+// binary16 high part and a binary16 rest, and hi*hi + hi*lo + lo*hi is
+// accumulated in binary32 (22 significant bits per operand; the dropped
+// lo*lo term is below 2^-22 of each product).  binary16 has a narrow
+// exponent range, so each product's B operand is scaled by a power of two
+// that brings its largest magnitude over the block just below 2^15, and A
+// is stored times 16 (the rests of its smallest cosines stay normal); the
+// accumulators are scaled back exactly.  Operand layouts of the instruction
+// (one wave): lane l supplies A[l mod 32][8 (l / 32) + e] and
+// B[8 (l / 32) + e][l mod 32], e < 8, and accumulator q of lane l is
+// C[8 (q / 4) + 4 (l / 32) + q mod 4][l mod 32].
 
-typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(8 * sizeof(_Float16)))) _Float16 f16x8;
 typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
 
 typedef float f32x2 __attribute__((ext_vector_type(2)));
-typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
-// High and low bfloat16 parts of two samples, packed two per word: hi =
-// RNE(v) and lo = RNE(v - hi) (the difference is exact in binary32).  The
-// conversions are the hardware's round-to-nearest-even packed convert.
+// High and low binary16 parts of two samples, packed two per word: hi =
+// RNE(v) and lo = RNE(v - hi) (the difference is exact in binary32).
 __device__ inline void split2(float v0, float v1, uint32_t& hi, uint32_t& lo) {
   const f32x2 v = {v0, v1};
-  const bf16x2 h = __builtin_convertvector(v, bf16x2);
+  const f16x2 h = __builtin_convertvector(v, f16x2);
   const f32x2 r = v - __builtin_convertvector(h, f32x2);
   hi = __builtin_bit_cast(uint32_t, h);
-  lo = __builtin_bit_cast(uint32_t, __builtin_convertvector(r, bf16x2));
+  lo = __builtin_bit_cast(uint32_t, __builtin_convertvector(r, f16x2));
+}
+
+// 2^k as a binary32 (k in [-126, 127]).
+__device__ inline float pow2f(int k) { return __uint_as_float(uint32_t(k + 127) << 23); }
+
+// The exponent k that brings the largest of the wave's magnitudes m (one
+// per lane) into [2^14, 2^15) when multiplied by 2^k; 0 for an all-zero
+// block.  Bounded so that 2^k and 2^-(k + 4) stay normal.
+__device__ inline int wave_scale_exp(float m) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+  if (!(m > 0.0f)) return 0;
+  const int e = int((__float_as_uint(m) >> 23) & 0xFFu) - 127;  // m in [2^e, 2^(e + 1))
+  return min(max(14 - e, -100), 100);
 }
 
 // The binary32 transform of the varblocks' LLF corners for one lane's
 // accumulators of the row product (acc[q] = sample (row j, column i) of the
-// region, i = 8 (q / 4) + 4 kh + q mod 4), written as their starting values.
-// Q[t]: the lane's row j of the corners after the column transform, t =
-// (varblock column) * cx + (LLF column v), cx = 2^MR LLF columns per
-// varblock of 8 cx samples; c1[n] = cos(pi (2 n + 1) / (16 cx)), and
-// cos(v phi) for v = 2, 3 follows from it (2 c^2 - 1, (4 c^2 - 3) c).
+// region, i = 8 (q / 4) + 4 kh + q mod 4), times `unit`, written as their
+// starting values.  Q[t]: the lane's row j of the corners after the column
+// transform, t = (varblock column) * cx + (LLF column v), cx = 2^MR LLF
+// columns per varblock of 8 cx samples; c1[n] = cos(pi (2 n + 1) / (16 cx)),
+// and cos(v phi) for v = 2, 3 follows from it (2 c^2 - 1, (4 c^2 - 3) c).
 template <int MR>
 __device__ inline void llf_row_init(f32x16& acc, const float (&Q)[4],
-                                    const float* __restrict__ c1, int kh) {
+                                    const float* __restrict__ c1, int kh, float unit) {
   constexpr int cx = 1 << MR;
 #pragma unroll
   for (int q = 0; q < 16; ++q) {
@@ -482,24 +502,22 @@ __device__ inline void llf_row_init(f32x16& acc, const float (&Q)[4],
         a = fmaf(Q[base + 3], fmaf(4.0f, c2, -3.0f) * c, a);
       }
     }
-    acc[q] = a;
+    acc[q] = a * unit;
   }
 }
 
 // One wave transforms the 32x32 block of cf starting at column col0, in
 // place.  m: the operand selector (column matrix | row matrix << 2, each
-// 0, 1, 2 for 8, 16, 32-sample varblock sides); Acol / Arow: the
-// DeviceTables::mfma_a operands [part][step][lane][8] of the column and row
-// matrices.  Only the high-frequency coefficients go through the split
-// products: each varblock's LLF corner (its top cy x cx coefficients, which
-// carry the DC and the largest values) is zeroed in the column product's
-// operand and transformed in binary32 on the side, the column step before
-// the products and the row step as the row product's starting accumulators
-// (the transform is linear, so the two parts sum to the whole).  Only the
-// calling wave touches the block, and the LDS accesses of one wave complete
-// in issue order, so the reads of the second product see the first
-// product's stores without a workgroup barrier; the caller synchronizes
-// before other waves read the block.
+// 0, 1, 2 for 8, 16, 32-sample varblock sides).  Only the high-frequency
+// coefficients go through the split products: each varblock's LLF corner
+// (its top cy x cx coefficients, which carry the DC and the largest values)
+// is zeroed in the column product's operand and transformed in binary32 on
+// the side, the column step before the products and the row step as the
+// row product's starting accumulators (the transform is linear, so the two
+// parts sum to the whole).  Only the calling wave touches the block, and
+// the LDS accesses of one wave complete in issue order, so the reads of the
+// second product see the first product's stores without a workgroup
+// barrier; the caller synchronizes before other waves read the block.
 __device__ inline void mfma_region(float (*cf)[kRecLd], int col0, int m,
                                    const DeviceTables* __restrict__ T, int lane) {
   const int j = lane & 31, kh = lane >> 5;
@@ -526,56 +544,62 @@ __device__ inline void mfma_region(float (*cf)[kRecLd], int col0, int m,
   const bool llf_col = (j & (nr - 1)) < cx;  // pass 0: column j holds LLF entries
 #pragma unroll
   for (int pass = 0; pass < 2; ++pass) {
-    const uint16_t* A = &T->mfma_a[pass == 0 ? mc : mr][0][0][0][0];
+    const uint16_t* A = &T->mfma_h[pass == 0 ? mc : mr][0][0][0][0];
+    // this lane's B operand values: pass 0 B = K[k][j] without the LLF
+    // corners, pass 1 B = Y^T[k][j] = Y[j][k]; k = 16 step + 8 kh + 2 e (+1).
+    // Read once for the block's largest magnitude and again to split (LDS
+    // reads are cheaper than keeping them live across the reduction).
+    auto bval = [&](int k) -> float {
+      if (pass == 0) {
+        const float x = cf[k][col0 + j];
+        return (llf_col && (k & (nc - 1)) < cy) ? 0.0f : x;
+      }
+      return cf[j][col0 + k];
+    };
+    float mx = 0.0f;
+#pragma unroll
+    for (int step = 0; step < 2; ++step)
+#pragma unroll
+      for (int e = 0; e < 8; ++e) mx = fmaxf(mx, fabsf(bval(16 * step + 8 * kh + e)));
+    const int sx = wave_scale_exp(mx);
+    const float sc = pow2f(sx), unit = pow2f(sx + 4), back = pow2f(-sx - 4);
     f32x16 acc;
     if (pass == 0) {
 #pragma unroll
       for (int q = 0; q < 16; ++q) acc[q] = 0.0f;
     } else {
-      // the row product accumulates onto the LLF corners' samples
+      // the row product accumulates onto the LLF corners' samples (in the
+      // products' scaled units)
       const float* c1 = T->llf_c1[mr];
-      if (mr == 0) llf_row_init<0>(acc, Q, c1, kh);
-      else if (mr == 1) llf_row_init<1>(acc, Q, c1, kh);
-      else llf_row_init<2>(acc, Q, c1, kh);
+      if (mr == 0) llf_row_init<0>(acc, Q, c1, kh, unit);
+      else if (mr == 1) llf_row_init<1>(acc, Q, c1, kh, unit);
+      else llf_row_init<2>(acc, Q, c1, kh, unit);
     }
 #pragma unroll
     for (int step = 0; step < 2; ++step) {
-      const bf16x8 ah = *reinterpret_cast<const bf16x8*>(A + ((0 * 2 + step) * 64 + lane) * 8);
-      const bf16x8 al = *reinterpret_cast<const bf16x8*>(A + ((1 * 2 + step) * 64 + lane) * 8);
+      const f16x8 ah = *reinterpret_cast<const f16x8*>(A + ((0 * 2 + step) * 64 + lane) * 8);
+      const f16x8 al = *reinterpret_cast<const f16x8*>(A + ((1 * 2 + step) * 64 + lane) * 8);
       u32x4 bh, bl;
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const int k = 16 * step + 8 * kh + 2 * e;
-        // pass 0: B = K[k][j] without the LLF corners; pass 1: B = Y^T[k][j] = Y[j][k]
-        float v0, v1;
-        if (pass == 0) {
-          v0 = cf[k][col0 + j];
-          v1 = cf[k + 1][col0 + j];
-          if (llf_col) {
-            if ((k & (nc - 1)) < cy) v0 = 0.0f;
-            if (((k + 1) & (nc - 1)) < cy) v1 = 0.0f;
-          }
-        } else {
-          v0 = cf[j][col0 + k];
-          v1 = cf[j][col0 + k + 1];
-        }
         uint32_t h, l;
-        split2(v0, v1, h, l);
+        split2(bval(k) * sc, bval(k + 1) * sc, h, l);
         bh[e] = h;
         bl[e] = l;
       }
-      const bf16x8 bH = __builtin_bit_cast(bf16x8, bh), bL = __builtin_bit_cast(bf16x8, bl);
-      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bH, acc, 0, 0, 0);
-      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bL, acc, 0, 0, 0);
-      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bH, acc, 0, 0, 0);
+      const f16x8 bH = __builtin_bit_cast(f16x8, bh), bL = __builtin_bit_cast(f16x8, bl);
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(al, bH, acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah, bL, acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah, bH, acc, 0, 0, 0);
     }
     // the stores depend on every read of this pass through acc
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
       const int i = 8 * (q >> 2) + 4 * kh + (q & 3);
       // pass 0: Y[i][j]; pass 1: S^T[i][j] = S[j][i]
-      if (pass == 0) cf[i][col0 + j] = acc[q];
-      else cf[j][col0 + i] = acc[q];
+      if (pass == 0) cf[i][col0 + j] = acc[q] * back;
+      else cf[j][col0 + i] = acc[q] * back;
     }
     __builtin_amdgcn_wave_barrier();
   }
@@ -668,6 +692,10 @@ __device__ __attribute__((always_inline)) inline void inverse_passes(
 }
 
 // One 64x32 tile (tile column tbx, row tby) of the reconstruction.
+// SPLIT: the variant with the split-precision transform (taken for the
+// regions of frames whose a.split is set); the plain variant keeps the
+// register budget of the binary32 passes alone.
+template <bool SPLIT>
 __device__ __attribute__((always_inline)) inline void recon_tile(const ReconArgs& a, int tbx, int tby) {
   __shared__ float coef[3][kRecTH][kRecLd];
   // DC samples per tile block (b = row * 8 + column), zero-padded so that a
@@ -755,7 +783,7 @@ __device__ __attribute__((always_inline)) inline void recon_tile(const ReconArgs
     if (s_bad[tid])
       for (int i = 0; i < 16; ++i) s_strat[tid][i] = kAbsent;
     int m = -1;
-    if (a.split) {
+    if (SPLIT && a.split) {
       // one DCT type over the whole region (then its varblocks tile it)
       const int s0 = s_strat[tid][0];
       bool uni = s0 != kAbsent && s0 != 1 && s0 != 2 && s0 != 3 && s0 < 12;
@@ -856,7 +884,7 @@ __device__ __attribute__((always_inline)) inline void recon_tile(const ReconArgs
   inverse_passes(coef, s_strat, s_owner, s_mma, T, tid);
 
   // Split-precision transform of the uniform regions (wave = channel).
-  if (a.split) {
+  if (SPLIT && a.split) {
     for (int r = 0; r < 2; ++r) {
       const int m = s_mma[r];
       if (m < 0) continue;
@@ -2545,6 +2573,73 @@ __global__ __launch_bounds__(kJ1Threads) void jpeg1_idct_kernel(J1IdctArgs a) {
   }
 }
 
+// M.6.3 block-gated Gaborish of one component plane (W x H pixels, whole
+// 8x8 blocks).  A workgroup takes 8 x 4 blocks, a wave one block row: lane
+// 8 r + b filters the 8 pixels of row r of block b (the J.4 3x3 kernel,
+// mirrored at the plane's edges), counts its interior pixels (offsets 1..6
+// both ways) that differ from the smoothed value by more than the
+// threshold, and the block's eight lanes sum their counts by cross-lane
+// exchanges; the block takes the smoothed values when the sum is below the
+// limit.
+struct J1GabArgs {
+  const float* in;
+  size_t in_stride;
+  float* out;
+  size_t out_stride;
+  int W, H;
+  float k0, k1, k2;  // centre, edge and diagonal weights (normalized)
+  float thr;
+  int limit;
+};
+
+__global__ __launch_bounds__(kJ1Threads) void jpeg1_gab_kernel(J1GabArgs a) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r = lane >> 3, b = lane & 7;
+  const int x0 = 8 * (blockIdx.x * 8 + b), y = 8 * (blockIdx.y * 4 + wave) + r;
+  const bool live = x0 < a.W && y < a.H;
+  float c[3][10];  // rows y - 1, y, y + 1; columns x0 - 1 .. x0 + 8
+  if (live) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      int yy = y + d - 1;
+      yy = yy < 0 ? 0 : (yy >= a.H ? a.H - 1 : yy);  // 6.5: the edge sample repeats
+      const float* row = a.in + size_t(yy) * a.in_stride;
+      const float4 l = *reinterpret_cast<const float4*>(row + x0);
+      const float4 h = *reinterpret_cast<const float4*>(row + x0 + 4);
+      c[d][1] = l.x; c[d][2] = l.y; c[d][3] = l.z; c[d][4] = l.w;
+      c[d][5] = h.x; c[d][6] = h.y; c[d][7] = h.z; c[d][8] = h.w;
+      c[d][0] = row[x0 > 0 ? x0 - 1 : 0];
+      c[d][9] = row[x0 + 8 < a.W ? x0 + 8 : a.W - 1];
+    }
+  } else {
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+#pragma unroll
+      for (int i = 0; i < 10; ++i) c[d][i] = 0.0f;
+  }
+  float sm[8];
+  int cnt = 0;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const float e = (c[0][i + 1] + c[2][i + 1]) + (c[1][i] + c[1][i + 2]);
+    const float g = (c[0][i] + c[0][i + 2]) + (c[2][i] + c[2][i + 2]);
+    sm[i] = fmaf(a.k0, c[1][i + 1], fmaf(a.k1, e, a.k2 * g));
+    if (i >= 1 && i <= 6) cnt += fabsf(c[1][i + 1] - sm[i]) > a.thr ? 1 : 0;
+  }
+  if (r == 0 || r == 7) cnt = 0;
+  cnt += __shfl_xor(cnt, 8);
+  cnt += __shfl_xor(cnt, 16);
+  cnt += __shfl_xor(cnt, 32);
+  if (!live) return;
+  const bool use = cnt < a.limit;
+  float o[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) o[i] = use ? sm[i] : c[1][i + 1];
+  float4* dst = reinterpret_cast<float4*>(a.out + size_t(y) * a.out_stride + x0);
+  dst[0] = make_float4(o[0], o[1], o[2], o[3]);
+  dst[1] = make_float4(o[4], o[5], o[6], o[7]);
+}
+
 struct J1ColorArgs {
   int W, H, ncomp;
   const float* pix[3];
@@ -2702,9 +2797,10 @@ __device__ inline int xcd_tile(int b, int G) {
 // (at most 96 VGPRs, 3 spilled), so that the six workgroups the LDS allows
 // fit; measured 4% faster than at 116 VGPRs.
 constexpr int kRecMinBlocks = 5;
+template <bool SPLIT>
 __global__ __launch_bounds__(kRecThreads, kRecMinBlocks) void recon_kernel(ReconArgs a, int tiles_x) {
   const int t = xcd_tile(blockIdx.x, gridDim.x);
-  recon_tile(a, t % tiles_x, t / tiles_x);
+  recon_tile<SPLIT>(a, t % tiles_x, t / tiles_x);
 }
 __global__ __launch_bounds__(kRecThreads, 4) void qco_kernel(QcoArgs a, int tiles_x) {
   const int t = xcd_tile(blockIdx.x, gridDim.x);
@@ -2798,7 +2894,7 @@ __device__ inline T const_load(const T* p) {
 // PERSIST: the workgroup walks tiles (TileRange); otherwise it takes tile
 // blockIdx.x only, which keeps the register allocation of the single-frame
 // kernels.
-template <bool PERSIST>
+template <bool PERSIST, bool SPLIT>
 // (The register cap of the single-frame kernel makes this one spill: its
 // arguments come from the descriptor table.)
 __global__ __launch_bounds__(kRecThreads) void recon_batch_kernel(BatchArgs b) {
@@ -2809,7 +2905,7 @@ __global__ __launch_bounds__(kRecThreads) void recon_batch_kernel(BatchArgs b) {
     const int lt = __builtin_amdgcn_readfirstlane(r.t - b.tile_start[f]);
     const int tx = const_load(&d->tiles_x);
     const ReconArgs a = const_load(&d->rec);
-    recon_tile(a, lt % tx, lt / tx);
+    recon_tile<SPLIT>(a, lt % tx, lt / tx);
     if (!PERSIST) break;
   }
 }
@@ -3042,9 +3138,9 @@ jxlr_status jxlr_create(jxlr_ctx** out, int device, const jxlr_dequant_encoding*
   }
   auto* ctx = new jxlr_ctx{device, nullptr, nullptr};
   hipError_t e = hipMalloc(&ctx->tables, sizeof(DeviceTables));
-  if (e == hipSuccess) e = hipMalloc(&ctx->status, sizeof(int));
+  if (e == hipSuccess) e = hipMalloc(&ctx->status, 2 * sizeof(int));
   if (e == hipSuccess) e = hipMemcpy(ctx->tables, host, sizeof(DeviceTables), hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMemset(ctx->status, 0, sizeof(int));
+  if (e == hipSuccess) e = hipMemset(ctx->status, 0, 2 * sizeof(int));
   delete host;
   if (e != hipSuccess) {
     jxlr_destroy(ctx);
@@ -3337,7 +3433,8 @@ jxlr_status jxlr_reconstruct(jxlr_ctx* ctx, const jxlr_frame_params* p, const jx
   if (st) return st;
   DeviceGuard g(ctx->device);
   if (!g.ok) return JXLR_E_HIP;
-  hipLaunchKernelGGL(recon_kernel, dim3(tiles_x(p) * tiles_y(p)), dim3(kRecThreads), 0, stream, a,
+  hipLaunchKernelGGL(p->idct_split ? recon_kernel<true> : recon_kernel<false>,
+                     dim3(tiles_x(p) * tiles_y(p)), dim3(kRecThreads), 0, stream, a,
                      tiles_x(p));
   return launch_status(hipGetLastError());
 }
@@ -3607,6 +3704,7 @@ jxlr_status j1_check(const jxlr_jpeg1_params* p) {
   if (!p) return JXLR_E_NULL;
   if (p->xsize < 1 || p->ysize < 1 || p->xsize > 65536 || p->ysize > 65536) return JXLR_E_SIZE;
   if (p->num_components != 1 && p->num_components != 3) return JXLR_E_PARAM;
+  if (p->gab < 0 || p->gab > 1) return JXLR_E_PARAM;
   for (int c = 0; c < p->num_components; ++c) {
     if (p->h_samp[c] < 1 || p->h_samp[c] > 2 || p->v_samp[c] < 1 || p->v_samp[c] > 2)
       return JXLR_E_PARAM;
@@ -3648,7 +3746,44 @@ size_t jxlr_jpeg1_workspace_bytes(const jxlr_jpeg1_params* p) {
   if (j1_check(p) != JXLR_OK) return 0;
   size_t n = 0;
   for (int c = 0; c < p->num_components; ++c) n += j1_plane_bytes(p, c);
-  return n;
+  return p->gab ? 2 * n : n;
+}
+
+jxlr_status jxlr_jpeg1_gaborish(jxlr_ctx* ctx, const jxlr_jpeg1_params* p, int32_t c,
+                                const float* pix_in, size_t in_stride, float* pix_out,
+                                size_t out_stride, hipStream_t stream) {
+  if (!ctx || !pix_in || !pix_out) return JXLR_E_NULL;
+  jxlr_status st = j1_check(p);
+  if (st) return st;
+  if (c < 0 || c >= p->num_components) return JXLR_E_PARAM;
+  if (pix_in == pix_out) return JXLR_E_PARAM;
+  int wib, hib;
+  j1_blocks(p, c, &wib, &hib);
+  if (in_stride < size_t(8) * wib || out_stride < size_t(8) * wib || in_stride % 4 ||
+      out_stride % 4 || reinterpret_cast<uintptr_t>(pix_in) % 16 ||
+      reinterpret_cast<uintptr_t>(pix_out) % 16)
+    return JXLR_E_SIZE;
+  J1GabArgs a{};
+  a.in = pix_in;
+  a.in_stride = in_stride;
+  a.out = pix_out;
+  a.out_stride = out_stride;
+  a.W = 8 * wib;
+  a.H = 8 * hib;
+  // J.4 weights from the side channel's bytes (exact in binary32), then
+  // normalized in binary64
+  const double w1 = p->gab_code[c][0] / 1024.0, w2 = p->gab_code[c][1] / 1024.0;
+  const double norm = 1.0 + 4.0 * w1 + 4.0 * w2;
+  a.k0 = float(1.0 / norm);
+  a.k1 = float(w1 / norm);
+  a.k2 = float(w2 / norm);
+  a.thr = float(p->gab_code[c][2]) / 16.0f;
+  a.limit = p->gab_code[c][3];
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return JXLR_E_HIP;
+  hipLaunchKernelGGL(jpeg1_gab_kernel, dim3((wib + 7) / 8, (hib + 3) / 4), dim3(kJ1Threads), 0,
+                     stream, a);
+  return launch_status(hipGetLastError());
 }
 
 jxlr_status jxlr_jpeg1_idct(jxlr_ctx* ctx, const jxlr_jpeg1_params* p, int32_t c,
@@ -3736,6 +3871,16 @@ jxlr_status jxlr_jpeg1_decode(jxlr_ctx* ctx, const jxlr_jpeg1_params* p,
       return st;
     pix[c] = pc;
   }
+  if (p->gab) {
+    // M.6.3 into the second half of the workspace
+    for (int c = 0; c < p->num_components; ++c) {
+      float* pg = reinterpret_cast<float*>(base);
+      base += j1_plane_bytes(p, c);
+      if ((st = jxlr_jpeg1_gaborish(ctx, p, c, pix[c], stride[c], pg, stride[c], stream)))
+        return st;
+      pix[c] = pg;
+    }
+  }
   return jxlr_jpeg1_color(ctx, p, pix, stride, rgb, rgb_stride, stream);
 }
 
@@ -3798,12 +3943,13 @@ jxlr_status launch_stage(jxlr_ctx* ctx, const jxlr_batch_plan* plan, int stage, 
     case JXLR_STAGE_INFO:
       hipLaunchKernelGGL(blockinfo_batch_kernel, dim3(gsz), dim3(kInfoThreads), 0, stream, b);
       break;
-    case JXLR_STAGE_RECON:
-      if (persist)
-        hipLaunchKernelGGL(recon_batch_kernel<true>, dim3(gsz), dim3(kRecThreads), 0, stream, b);
-      else
-        hipLaunchKernelGGL(recon_batch_kernel<false>, dim3(gsz), dim3(kRecThreads), 0, stream, b);
+    case JXLR_STAGE_RECON: {
+      const bool sp = plan->any_split != 0;
+      auto k = persist ? (sp ? recon_batch_kernel<true, true> : recon_batch_kernel<true, false>)
+                       : (sp ? recon_batch_kernel<false, true> : recon_batch_kernel<false, false>);
+      hipLaunchKernelGGL(k, dim3(gsz), dim3(kRecThreads), 0, stream, b);
       break;
+    }
     case JXLR_STAGE_EPF:
       if (persist)
         hipLaunchKernelGGL(epf_batch_kernel<true>, dim3(gsz), dim3(kEpfThreads), 0, stream, b);
@@ -3838,7 +3984,7 @@ size_t jxlr_batch_workspace_bytes(int n, const jxlr_frame_params* p) {
 
 jxlr_status jxlr_batch_prepare(jxlr_ctx* ctx, int n, const jxlr_frame_params* p,
                                const jxlr_frame_io* io, void* ws, size_t ws_bytes,
-                               jxlr_batch_plan* plan) {
+                               jxlr_batch_plan* plan, hipStream_t stream) {
   if (!ctx || !p || !io || !ws || !plan) return JXLR_E_NULL;
   if (n <= 0) return JXLR_E_SIZE;
   for (int i = 0; i < n; ++i) {
@@ -3885,16 +4031,21 @@ jxlr_status jxlr_batch_prepare(jxlr_ctx* ctx, int n, const jxlr_frame_params* p,
   }
   DeviceGuard g(ctx->device);
   if (!g.ok) return JXLR_E_HIP;
-  hipError_t e = hipMemcpy(base + L.frames, frames.data(), sizeof(FrameDesc) * n,
-                           hipMemcpyHostToDevice);
+  // the descriptors are copied in order on the caller's stream (after any
+  // earlier batch on it that may still read this workspace) and the call
+  // returns once they are in place, so the host arrays may go away
+  hipError_t e = hipMemcpyAsync(base + L.frames, frames.data(), sizeof(FrameDesc) * n,
+                                hipMemcpyHostToDevice, stream);
   if (e == hipSuccess)
-    e = hipMemcpy(base + L.tile_frame, tframe.data(), sizeof(int) * tframe.size(),
-                  hipMemcpyHostToDevice);
+    e = hipMemcpyAsync(base + L.tile_frame, tframe.data(), sizeof(int) * tframe.size(),
+                       hipMemcpyHostToDevice, stream);
   if (e == hipSuccess)
-    e = hipMemcpy(base + L.tile_start, tstart.data(), sizeof(int) * (n + 1), hipMemcpyHostToDevice);
+    e = hipMemcpyAsync(base + L.tile_start, tstart.data(), sizeof(int) * (n + 1),
+                       hipMemcpyHostToDevice, stream);
   if (e == hipSuccess)
-    e = hipMemcpy(base + L.region_start, rstart.data(), sizeof(int) * (n + 1),
-                  hipMemcpyHostToDevice);
+    e = hipMemcpyAsync(base + L.region_start, rstart.data(), sizeof(int) * (n + 1),
+                       hipMemcpyHostToDevice, stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
   if (e != hipSuccess) return JXLR_E_HIP;
   plan->ws = ws;
   plan->ws_bytes = L.total;
@@ -3902,6 +4053,8 @@ jxlr_status jxlr_batch_prepare(jxlr_ctx* ctx, int n, const jxlr_frame_params* p,
   plan->total_tiles = tstart[n];
   plan->total_regions = rstart[n];
   plan->max_epf_iters = max_epf;
+  plan->any_split = 0;
+  for (int i = 0; i < n; ++i) plan->any_split |= p[i].idct_split;
   plan->frames_offset = L.frames;
   plan->tile_frame_offset = L.tile_frame;
   plan->tile_start_offset = L.tile_start;
@@ -3959,7 +4112,9 @@ jxlr_status jxlr_autotune(jxlr_ctx* ctx, const jxlr_batch_plan* plan, int reps,
     return JXLR_E_HIP;
   }
   const int stages[3] = {JXLR_STAGE_RECON, JXLR_STAGE_EPF, JXLR_STAGE_FINISH};
-  const void* kerns[3] = {reinterpret_cast<const void*>(recon_batch_kernel<true>),
+  const void* kerns[3] = {plan->any_split
+                              ? reinterpret_cast<const void*>(recon_batch_kernel<true, true>)
+                              : reinterpret_cast<const void*>(recon_batch_kernel<true, false>),
                           reinterpret_cast<const void*>(epf_batch_kernel<true>),
                           reinterpret_cast<const void*>(finish_batch_kernel<true>)};
   const int threads[3] = {kRecThreads, kEpfThreads, fin_threads<kFinRowsBatch>()};
@@ -4029,12 +4184,15 @@ jxlr_status jxlr_decode_batch(jxlr_ctx* ctx, int n, const jxlr_frame_params* p,
                               const jxlr_frame_io* io, void* ws, size_t ws_bytes,
                               hipStream_t stream) {
   jxlr_batch_plan plan;
-  jxlr_status st = jxlr_batch_prepare(ctx, n, p, io, ws, ws_bytes, &plan);
+  jxlr_status st = jxlr_batch_prepare(ctx, n, p, io, ws, ws_bytes, &plan, stream);
   if (st) return st;
   return jxlr_batch_run(ctx, &plan, nullptr, stream);
 }
 
 }  // extern "C"
+
+// status[1] = the sticky flag status[0], which is cleared in the same step.
+__global__ void status_take_kernel(int* status) { status[1] = atomicExch(status, 0); }
 
 struct jxlr_graph {
   int device;
@@ -4089,16 +4247,16 @@ jxlr_status jxlr_get_device_status(jxlr_ctx* ctx, hipStream_t stream) {
   if (!ctx) return JXLR_E_NULL;
   DeviceGuard g(ctx->device);
   if (!g.ok) return JXLR_E_HIP;
+  // read and clear in one atomic exchange on the device (a flag set by other
+  // work between a read and a separate clear would be lost)
+  hipLaunchKernelGGL(status_take_kernel, dim3(1), dim3(1), 0, stream, ctx->status);
+  if (hipGetLastError() != hipSuccess) return JXLR_E_HIP;
   int h = 0;
-  if (hipMemcpyAsync(&h, ctx->status, sizeof(int), hipMemcpyDeviceToHost, stream) != hipSuccess)
+  if (hipMemcpyAsync(&h, ctx->status + 1, sizeof(int), hipMemcpyDeviceToHost, stream) !=
+      hipSuccess)
     return JXLR_E_HIP;
   if (hipStreamSynchronize(stream) != hipSuccess) return JXLR_E_HIP;
-  if (h) {
-    if (hipMemsetAsync(ctx->status, 0, sizeof(int), stream) != hipSuccess) return JXLR_E_HIP;
-    if (hipStreamSynchronize(stream) != hipSuccess) return JXLR_E_HIP;
-    return JXLR_E_DEVICE_VALIDATION;
-  }
-  return JXLR_OK;
+  return h ? JXLR_E_DEVICE_VALIDATION : JXLR_OK;
 }
 
 }  // extern "C"

@@ -498,6 +498,31 @@ uint16_t bf16_rne(float v) {
   return uint16_t((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
 }
 
+uint16_t f16_rne(double v) {
+  // sign, then the magnitude as an integer count of the format's spacing at
+  // its exponent (2^-24 for subnormals), rounded to nearest even
+  const uint16_t sign = v < 0 ? 0x8000u : 0u;
+  double a = std::fabs(v);
+  if (a == 0.0) return sign;
+  int e;
+  std::frexp(a, &e);  // a = f 2^e, f in [0.5, 1)
+  int ulp_exp = std::max(e - 11, -24);  // spacing 2^(e - 11) for normals
+  double q = std::nearbyint(std::ldexp(a, -ulp_exp));  // ties to even (default mode)
+  if (q >= 2048.0) {  // rounded up into the next binade
+    q /= 2.0;
+    ulp_exp += 1;
+  }
+  const int biased = ulp_exp + 25;  // exponent field of a normal with this spacing
+  if (q < 1024.0) return uint16_t(sign | uint16_t(q));  // subnormal (ulp_exp == -24)
+  return uint16_t(sign | uint16_t(biased << 10) | (uint16_t(q) & 0x3FFu));
+}
+
+double f16_value(uint16_t h) {
+  const int ex = (h >> 10) & 31, m = h & 1023;
+  const double v = ex ? std::ldexp(1024.0 + m, ex - 25) : std::ldexp(double(m), -24);
+  return (h & 0x8000u) ? -v : v;
+}
+
 namespace {
 float bf16_value(uint16_t h) {
   const uint32_t u = uint32_t(h) << 16;
@@ -519,6 +544,9 @@ void build_mfma_operands(DeviceTables* t) {
           const uint16_t lo = bf16_rne(float(a - double(bf16_value(hi))));
           t->mfma_a[m][0][step][l][e] = hi;
           t->mfma_a[m][1][step][l][e] = lo;
+          const uint16_t hh = f16_rne(16.0 * a);
+          t->mfma_h[m][0][step][l][e] = hh;
+          t->mfma_h[m][1][step][l][e] = f16_rne(16.0 * a - f16_value(hh));
         }
     for (int n = 0; n < 32; ++n)
       for (int u = 0; u < 4; ++u)

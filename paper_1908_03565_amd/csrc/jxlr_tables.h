@@ -80,6 +80,10 @@ struct DeviceTables {
   // A-operand order of a 32x32x16 matrix instruction: element e of lane l in
   // k-step t is A[l mod 32][16 t + 8 (l / 32) + e].
   alignas(16) uint16_t mfma_a[3][2][2][64][8];
+  // The same matrices times 16, as binary16 high parts (part 0, rounded to
+  // nearest even) and rests (part 1): the split form's A operands (times 16
+  // so that the rests of the smallest cosines stay normal numbers).
+  alignas(16) uint16_t mfma_h[3][2][2][64][8];
   // The same cosines in binary32 for the varblocks' LLF corners, which the
   // split form transforms outside the matrix products: llf_cos[m][n][u] =
   // cos(pi (2 n + 1) u / (2 N)), N = 8 << m, n < N, u < 4 (zero for u >= N / 8),
@@ -158,5 +162,9 @@ void srgb_thresholds(int bits, float* thr);
 bool srgb_bucket_starts(uint8_t* start);
 // bfloat16 bit pattern of v rounded to nearest, ties to even.
 uint16_t bf16_rne(float v);
+// binary16 bit pattern of v rounded to nearest, ties to even (finite v
+// within the binary16 range), and its value.
+uint16_t f16_rne(double v);
+double f16_value(uint16_t h);
 
 }  // namespace jxlr

@@ -112,6 +112,7 @@ class BatchPlan(C.Structure):
         ("frames_offset", C.c_size_t), ("tile_frame_offset", C.c_size_t),
         ("tile_start_offset", C.c_size_t),
         ("region_start_offset", C.c_size_t),
+        ("any_split", C.c_int),
     ]
 
 
@@ -130,7 +131,8 @@ STAGE_INFO, STAGE_RECON, STAGE_EPF, STAGE_FINISH = 0, 1, 2, 3
 class Jpeg1Params(C.Structure):
     _fields_ = [("xsize", C.c_int32), ("ysize", C.c_int32), ("num_components", C.c_int32),
                 ("h_samp", C.c_int32 * 3), ("v_samp", C.c_int32 * 3),
-                ("quant", (C.c_int32 * 64) * 3)]
+                ("quant", (C.c_int32 * 64) * 3),
+                ("gab", C.c_int32), ("gab_code", (C.c_uint8 * 4) * 3)]
 
 
 def jpeg1_params(j):
@@ -141,6 +143,11 @@ def jpeg1_params(j):
         p.h_samp[c], p.v_samp[c] = j["hs"][c], j["vs"][c]
         for i, q in enumerate(np.asarray(j["quant"][c]).ravel()):
             p.quant[c][i] = int(q)
+    if j.get("gab") is not None:
+        p.gab = 1
+        for c, code in enumerate(j["gab"]):
+            for i, v in enumerate(code):
+                p.gab_code[c][i] = int(v)
     return p
 
 
@@ -188,6 +195,8 @@ _SIGS = {
     "jxlr_jpeg1_workspace_bytes": ([C.c_void_p], C.c_size_t),
     "jxlr_jpeg1_idct": ([C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_size_t, C.c_void_p,
                          C.c_size_t, C.c_void_p], C.c_int),
+    "jxlr_jpeg1_gaborish": ([C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_size_t, C.c_void_p,
+                             C.c_size_t, C.c_void_p], C.c_int),
     "jxlr_jpeg1_color": ([C.c_void_p, C.c_void_p, C.c_void_p * 3, C.c_size_t * 3,
                           C.c_void_p * 3, C.c_size_t, C.c_void_p], C.c_int),
     "jxlr_jpeg1_decode": ([C.c_void_p, C.c_void_p, C.c_void_p * 3, C.c_size_t * 3,
@@ -202,7 +211,7 @@ _SIGS = {
                      C.c_size_t, C.c_void_p], C.c_int),
     "jxlr_batch_workspace_bytes": ([C.c_int, C.POINTER(FrameParams)], C.c_size_t),
     "jxlr_batch_prepare": ([C.c_void_p, C.c_int, C.POINTER(FrameParams), C.POINTER(FrameIO),
-                            C.c_void_p, C.c_size_t, C.POINTER(BatchPlan)], C.c_int),
+                            C.c_void_p, C.c_size_t, C.POINTER(BatchPlan), C.c_void_p], C.c_int),
     "jxlr_batch_run": ([C.c_void_p, C.POINTER(BatchPlan), C.POINTER(LaunchConfig), C.c_void_p],
                        C.c_int),
     "jxlr_batch_stage": ([C.c_void_p, C.POINTER(BatchPlan), C.c_int, C.c_int, C.c_int, C.c_int,
@@ -459,6 +468,11 @@ class Context:
                                      pix.data_ptr(), pix.shape[1], _stream_handle(stream)),
                "jpeg1_idct")
 
+    def jpeg1_gaborish(self, jp, c, pix_in, pix_out, stream=None):
+        _check(lib().jxlr_jpeg1_gaborish(self.handle, C.byref(jp), c, pix_in.data_ptr(),
+                                         pix_in.shape[1], pix_out.data_ptr(), pix_out.shape[1],
+                                         _stream_handle(stream)), "jpeg1_gaborish")
+
     def jpeg1_color(self, jp, pix, rgb, stream=None):
         ptr = (C.c_void_p * 3)(*([q.data_ptr() for q in pix] + [None] * (3 - len(pix))))
         strides = (C.c_size_t * 3)(*([q.shape[1] for q in pix] + [0] * (3 - len(pix))))
@@ -569,15 +583,16 @@ class Context:
             raise JxlrError(7, "batch_workspace_bytes")
         return torch.empty(n, dtype=torch.uint8, device=f"cuda:{self.device}")
 
-    def batch_prepare(self, ps, ios, ws):
+    def batch_prepare(self, ps, ios, ws, stream=None):
         """ps, ios: lists of FrameParams / FrameIO; ws: device workspace tensor.
-        Returns the plan (keeps the host arrays alive with it)."""
+        The descriptors are written in order on `stream` (default: the current
+        stream), which the call synchronizes.  Returns the plan."""
         n = len(ps)
         parr = (FrameParams * n)(*ps)
         iarr = (FrameIO * n)(*ios)
         plan = BatchPlan()
         _check(lib().jxlr_batch_prepare(self.handle, n, parr, iarr, ws.data_ptr(), ws.numel(),
-                                        C.byref(plan)), "batch_prepare")
+                                        C.byref(plan), _stream_handle(stream)), "batch_prepare")
         return plan
 
     def batch_run(self, plan, cfg=None, stream=None):

@@ -30,14 +30,28 @@ from . import jxlr as J
 _OUT_BYTES = {0: 4, 1: 1, 2: 2}
 
 
+_ALLOC = 512  # torch's caching allocator rounds every block up to this
+
+
+def _rounded(n):
+    return -(-n // _ALLOC) * _ALLOC
+
+
 def footprint_bytes(p):
-    """Device bytes one request holds while admitted: AC (int32) and DC
-    planes, maps, chroma-from-luma tiles, the decode workspace (block info and
-    XYB planes), the output planes, and a share of the batch header."""
+    """Device bytes one request holds while admitted, each buffer rounded as
+    the allocator rounds it: the AC (int32) and DC planes, the three maps,
+    the chroma-from-luma tiles, the output planes, and its part of the batch
+    workspace (the library's per-frame workspace plus its share of the
+    descriptor header: a frame descriptor, one int per 64x32 tile and its
+    prefix entries, which is what a batch of this frame alone adds over
+    jxlr_workspace_bytes)."""
     W, H = p.xsize, p.ysize
     Wb, Hb = (W + 7) // 8, (H + 7) // 8
-    inputs = 3 * 64 * Wb * Hb * 4 + 3 * Wb * Hb * 4 + 3 * Wb * Hb + 2 * ((W + 63) // 64) * ((H + 63) // 64) * 4
-    return inputs + J.workspace_bytes(p) + 3 * W * H * _OUT_BYTES[p.out_format] + 4096
+    Wt, Ht = (W + 63) // 64, (H + 63) // 64
+    inputs = (_rounded(3 * 64 * Wb * Hb * 4) + _rounded(3 * Wb * Hb * 4) + 3 * _rounded(Wb * Hb) +
+              2 * _rounded(Wt * Ht * 4))
+    out = _rounded(3 * W * H * _OUT_BYTES[p.out_format])
+    return inputs + out + J.batch_workspace_bytes([p])
 
 
 class Request:
@@ -71,6 +85,9 @@ class Server:
         self.streams = [torch.cuda.Stream(device=self.dev) for _ in range(n_streams)]
         self.up_stream = torch.cuda.Stream(device=self.dev)
         self.down_stream = torch.cuda.Stream(device=self.dev)
+        # batch descriptors are written on a stream of their own, which the
+        # prepare call synchronizes (only its own copies are ever on it)
+        self.prep_stream = torch.cuda.Stream(device=self.dev)
         self.next_stream = 0
         self.used = 0
         self.peak_used = 0
@@ -112,8 +129,10 @@ class Server:
             with torch.cuda.stream(s):
                 for r in batch:
                     s.wait_event(r.ev_up)
+                # a fresh workspace per batch, held until the batch is done
                 ws = self.ctx.batch_workspace(ps)
-                plan = self.ctx.batch_prepare(ps, [r.df.io(r.out) for r in batch], ws)
+                plan = self.ctx.batch_prepare(ps, [r.df.io(r.out) for r in batch], ws,
+                                              stream=self.prep_stream)
                 self.ctx.batch_run(plan, stream=s)
                 ev = torch.cuda.Event()
                 ev.record(s)

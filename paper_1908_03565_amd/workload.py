@@ -449,6 +449,15 @@ def jpeg1(W, H, seed, hs=(2, 1, 1), vs=(2, 1, 1), grey=False):
             "vs": list(vs[:n]), "name": f"jpeg1_{W}x{H}_{'grey' if grey else 'ycbcr'}"}
 
 
+def jpeg1_gab_codes(seed, n=3):
+    """Synthetic M.6.3 side-channel bytes per component: gab_weight1 * 1024,
+    gab_weight2 * 1024 (around the J.4 defaults' 118 and 63), threshold * 16
+    (0.5 to 6) and limit (1 to 36 of a block's interior pixels)."""
+    rng = np.random.default_rng(seed)
+    return [[int(rng.integers(60, 181)), int(rng.integers(20, 101)), int(rng.integers(8, 97)),
+             int(rng.integers(1, 37))] for _ in range(n)]
+
+
 def j1():
     """JPEG1 rasterization workload: 4096 x 4096, 4:2:0."""
     f = jpeg1(4096, 4096, seed=9)

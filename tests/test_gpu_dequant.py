@@ -64,6 +64,7 @@ def _run(ctx, f, encs, **over):
     p = J.params(f["xsize"], f["ysize"], out_format=f["out_format"], **kw)
     assert J.validate_maps_host(p, f) == 0
     gpu = P.gpu_stages(ctx, p, J.DeviceFrame(f))
+    kw.pop("idct_split", None)  # the library's transform arithmetic only
     q = O.params(f["xsize"], f["ysize"], dq_enc=encs, **kw)
     return p, q, gpu, O.decode_stages(q, f)
 

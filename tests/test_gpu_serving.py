@@ -45,9 +45,17 @@ def test_served_equals_alone(ctx, split):
                                                     out_format=fr["out_format"], **fr["params"])))
     budget = int(0.35 * sum(fps))
     assert budget >= max(fps)
+    torch.cuda.synchronize()
+    base = torch.cuda.memory_allocated()
+    torch.cuda.reset_peak_memory_stats()
     srv, wall = serving.run(ctx, arrivals, make, budget, split=split, max_batch=8, keep_every=1)
     assert len(srv.done) == len(arrivals)
     assert srv.peak_used <= budget
+    # the accounting matches what the allocator actually handed out (batch
+    # headers round per batch, not per request: a few KiB of slack)
+    peak = torch.cuda.max_memory_allocated() - base
+    print(f"budget {budget}, admitted peak {srv.peak_used}, allocated peak {peak}")
+    assert peak <= budget + (64 << 10)
     assert srv.batches > 1 and max(srv.batch_sizes) > 1
     assert ctx.device_status() == 0
     for r in srv.done:

@@ -262,6 +262,19 @@ def test_encoded_dequant_tables_match_oracle(shim):
             O.dequant_matrix(s, 0, encs)
 
 
+def test_create_rejects_ill_formed_encodings_before_any_device_call():
+    # the encodings are checked while the tables are built, before the
+    # device is touched, so this runs without a GPU
+    for s, e in ((4, {"mode": 1, "params": [[1.0] * 3] * 3}), (6, {"mode": 7, "copy_from": 9}),
+                 (0, {"mode": 6, "num_bands": 2, "num_ecc_bands": 1,
+                      "dist_bands": [[0.0, 0.0]] * 3, "ecc_bands": [[0.0]] * 3})):
+        encs = [{"mode": 0}] * 15
+        encs[s] = e
+        h = C.c_void_p()
+        st = J.lib().jxlr_create(C.byref(h), 0, C.cast(J.dequant_encodings(encs), C.c_void_p))
+        assert st == 6 and not h.value, (s, e)
+
+
 def test_cfl_and_dc_multiplier_helpers():
     # Annex G on every byte value, exact in binary32
     v = np.arange(256, dtype=np.uint8)
