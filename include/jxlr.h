@@ -325,6 +325,20 @@ size_t jxlr_workspace_bytes(const jxlr_frame_params* p);
 jxlr_status jxlr_decode(jxlr_ctx* ctx, const jxlr_frame_params* p, const jxlr_frame_io* io,
                         void* ws, size_t ws_bytes, hipStream_t stream);
 
+/* jxlr_decode for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation): the
+ * workspace is a fixed array in the library's code object, one per device
+ * (jxlr_noalloc_scratch_bytes() bytes, 64 MiB: a 1920 x 1080 frame with EPF
+ * fits), whose address jxlr_create looks up; the call allocates nothing.
+ * Inputs and outputs as for jxlr_decode.  JXLR_E_WORKSPACE (before any
+ * launch) when jxlr_workspace_bytes(p) exceeds the array.  Every call on one
+ * device shares that device's array: calls that overlap on one device (other
+ * streams, other contexts, other host threads) race and give undefined
+ * results; calls ordered on one stream are safe. */
+jxlr_status jxlr_decode_noalloc(jxlr_ctx* ctx, const jxlr_frame_params* p,
+                                const jxlr_frame_io* io, hipStream_t stream);
+size_t jxlr_noalloc_scratch_bytes(void);
+
 /* ---- stage entry points (the pieces jxlr_decode runs, for testing and for
  * callers that keep XYB) --------------------------------------------------
  * XYB planes are float [3][ysize][xsize] with row stride xyb_stride elements,

@@ -38,7 +38,17 @@ struct jxlr_ctx {
   int device;
   DeviceTables* tables;  // device memory
   int* status;           // device memory: [0] the sticky validation flag, [1] its last read
+  void* scratch;         // this device's copy of `scratch` (jxlr_decode_noalloc)
 };
+
+namespace {
+// Workspace of jxlr_decode_noalloc, for callers that cannot allocate: one
+// array per device in the code object, held until the process ends.  Host
+// code never passes its name to a kernel (on the host it is a stand-in, not
+// a device address); jxlr_create looks up this device's address once.
+constexpr size_t kNoallocScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) uint8_t scratch[kNoallocScratchBytes];
+}  // namespace
 
 namespace {
 
@@ -3136,8 +3146,10 @@ jxlr_status jxlr_create(jxlr_ctx** out, int device, const jxlr_dequant_encoding*
     delete host;
     return JXLR_E_HIP;
   }
-  auto* ctx = new jxlr_ctx{device, nullptr, nullptr};
-  hipError_t e = hipMalloc(&ctx->tables, sizeof(DeviceTables));
+  auto* ctx = new jxlr_ctx{device, nullptr, nullptr, nullptr};
+  // this device's copy of the scratch array (the device is current here)
+  hipError_t e = hipGetSymbolAddress(&ctx->scratch, HIP_SYMBOL(scratch));
+  if (e == hipSuccess) e = hipMalloc(&ctx->tables, sizeof(DeviceTables));
   if (e == hipSuccess) e = hipMalloc(&ctx->status, 2 * sizeof(int));
   if (e == hipSuccess) e = hipMemcpy(ctx->tables, host, sizeof(DeviceTables), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemset(ctx->status, 0, 2 * sizeof(int));
@@ -3694,6 +3706,21 @@ jxlr_status jxlr_decode(jxlr_ctx* ctx, const jxlr_frame_params* p, const jxlr_fr
   }
   return jxlr_finish(ctx, p, &iop, cur, stride, stream);
 }
+
+jxlr_status jxlr_decode_noalloc(jxlr_ctx* ctx, const jxlr_frame_params* p,
+                                const jxlr_frame_io* io, hipStream_t stream) {
+  if (!ctx || !io) return JXLR_E_NULL;
+  jxlr_status st = check_params(p);
+  if (st) return st;
+  if (!ctx->scratch) return JXLR_E_HIP;
+  const size_t need = jxlr_workspace_bytes(p);
+  if (need > kNoallocScratchBytes) return JXLR_E_WORKSPACE;
+  // every stage writes its part of the workspace before any stage reads it,
+  // so nothing is cleared between calls
+  return jxlr_decode(ctx, p, io, ctx->scratch, kNoallocScratchBytes, stream);
+}
+
+size_t jxlr_noalloc_scratch_bytes(void) { return kNoallocScratchBytes; }
 
 }  // extern "C"
 

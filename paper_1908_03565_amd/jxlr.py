@@ -174,6 +174,9 @@ _SIGS = {
     "jxlr_workspace_bytes": ([C.POINTER(FrameParams)], C.c_size_t),
     "jxlr_decode": ([C.c_void_p, C.POINTER(FrameParams), C.POINTER(FrameIO), C.c_void_p,
                      C.c_size_t, C.c_void_p], C.c_int),
+    "jxlr_decode_noalloc": ([C.c_void_p, C.POINTER(FrameParams), C.POINTER(FrameIO), C.c_void_p],
+                            C.c_int),
+    "jxlr_noalloc_scratch_bytes": ([], C.c_size_t),
     "jxlr_block_info": ([C.c_void_p, C.POINTER(FrameParams), C.POINTER(FrameIO), C.c_void_p,
                          C.c_void_p], C.c_int),
     "jxlr_reconstruct": ([C.c_void_p, C.POINTER(FrameParams), C.POINTER(FrameIO), C.c_void_p,
@@ -574,6 +577,12 @@ class Context:
         io = df.io(out) if io is None else io
         _check(lib().jxlr_decode(self.handle, C.byref(p), C.byref(io), ws.data_ptr(),
                                  ws.numel(), _stream_handle(stream)), "decode")
+
+    def decode_noalloc(self, p, df, out, stream=None, io=None):
+        """jxlr_decode on the library's own per-device scratch array."""
+        io = df.io(out) if io is None else io
+        _check(lib().jxlr_decode_noalloc(self.handle, C.byref(p), C.byref(io),
+                                         _stream_handle(stream)), "decode_noalloc")
 
     # --- batches ---
     def batch_workspace(self, ps):
