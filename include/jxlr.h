@@ -512,11 +512,26 @@ jxlr_status jxlr_jpeg1_decode(jxlr_ctx* ctx, const jxlr_jpeg1_params* p,
                               hipStream_t stream);
 
 /* ---- batches of frames ------------------------------------------------------
- * A batch decodes n independent frames (each with its own sizes, parameters
- * and inputs) in one launch per stage: the tiles of all frames form one list
- * that persistent workgroups walk, so small frames share the GPU instead of
- * each leaving most of it idle.  Results are bit-identical to jxlr_decode of
- * each frame alone. */
+ * A batch decodes n independent frames (each with its own sizes, parameters,
+ * options and inputs) in one launch per stage: the tiles of all frames form
+ * one list that persistent workgroups walk, so small frames share the GPU
+ * instead of each leaving most of it idle.  The options (AC prediction, the
+ * quantization constraint, patches, noise, dots, splines) run as option
+ * stages: one launch each over the frames that use it.  Results are
+ * bit-identical to jxlr_decode of each frame alone. */
+
+/* Stages of a batch, for jxlr_batch_stage.  The tile stages INFO, RECON, EPF
+ * and FINISH take every frame; the option stages PRED (Annex H, before
+ * RECON), QCO (J.3, after the EPF passes), PATCHES (K.3), NOISE (K.5
+ * channels), GABORISH (J.4 as its own pass, for frames with dots or
+ * splines), DOTS (K.2) and SPLINES (K.4), in this order before FINISH, take
+ * the frames that use them. */
+enum {
+  JXLR_STAGE_INFO = 0, JXLR_STAGE_RECON = 1, JXLR_STAGE_EPF = 2, JXLR_STAGE_FINISH = 3,
+  JXLR_STAGE_PRED = 4, JXLR_STAGE_QCO = 5, JXLR_STAGE_PATCHES = 6, JXLR_STAGE_NOISE = 7,
+  JXLR_STAGE_GABORISH = 8, JXLR_STAGE_DOTS = 9, JXLR_STAGE_SPLINES = 10
+};
+#define JXLR_BATCH_OPT_STAGES 7 /* JXLR_STAGE_PRED .. JXLR_STAGE_SPLINES */
 
 /* Device workspace for a batch: a descriptor header plus, per frame, what
  * jxlr_workspace_bytes(&p[i]) names; 0 if n <= 0 or a parameter set is out of
@@ -533,6 +548,13 @@ typedef struct jxlr_batch_plan {
   int max_epf_iters;
   size_t frames_offset, tile_frame_offset, tile_start_offset, region_start_offset;
   int any_split;     /* some frame has idct_split set */
+  int any_noise;     /* some frame adds noise */
+  /* option stage JXLR_STAGE_PRED + k: the frames that take it, its
+   * workgroups over them, and where its table and unit prefix sit in ws */
+  int opt_frames[JXLR_BATCH_OPT_STAGES];
+  int opt_units[JXLR_BATCH_OPT_STAGES];
+  size_t opt_entries_offset[JXLR_BATCH_OPT_STAGES];
+  size_t opt_start_offset[JXLR_BATCH_OPT_STAGES];
 } jxlr_batch_plan;
 
 /* Schedule of the four persistent stage kernels.  grid_*: workgroup count;
@@ -551,9 +573,6 @@ typedef struct jxlr_launch_config {
   int order_finish;
 } jxlr_launch_config;
 
-/* Stages of a batch, for jxlr_batch_stage. */
-enum { JXLR_STAGE_INFO = 0, JXLR_STAGE_RECON = 1, JXLR_STAGE_EPF = 2, JXLR_STAGE_FINISH = 3 };
-
 /* Validates every frame as the single-frame entry points do and writes the
  * batch descriptors into `ws` (device memory, ws_bytes >=
  * jxlr_batch_workspace_bytes(n, p)).  The copies are ordered on `stream`
@@ -567,15 +586,19 @@ jxlr_status jxlr_batch_prepare(jxlr_ctx* ctx, int n, const jxlr_frame_params* p,
                                jxlr_batch_plan* plan, hipStream_t stream);
 
 /* Enqueues the whole path for every frame of the plan on `stream`: block
- * info, reconstruction, max_epf_iters EPF passes (a frame with fewer passes
- * sits out the rest) and finish.  cfg may be NULL. */
+ * info, AC prediction, reconstruction, max_epf_iters EPF passes (a frame
+ * with fewer passes sits out the rest), the option stages from QCO to
+ * SPLINES, and finish; a stage that no frame takes launches nothing.  cfg
+ * may be NULL. */
 jxlr_status jxlr_batch_run(jxlr_ctx* ctx, const jxlr_batch_plan* plan,
                            const jxlr_launch_config* cfg, hipStream_t stream);
 
 /* Enqueues one stage of a prepared batch (EPF: pass epf_pass, reading and
- * writing the XYB buffer pair that pass uses).  Each stage reads what the
- * stage before it wrote, so stages must run in jxlr_batch_run's order for a
- * correct result; repeating one stage alone is idempotent. */
+ * writing the XYB buffers that pass uses; option stages ignore grid and
+ * order).  Each stage reads what the stage before it wrote, so stages must
+ * run in jxlr_batch_run's order for a correct result.  Repeating one tile
+ * stage alone is idempotent; QCO, PATCHES, DOTS and SPLINES change their
+ * buffer in place and are not. */
 jxlr_status jxlr_batch_stage(jxlr_ctx* ctx, const jxlr_batch_plan* plan, int stage, int grid,
                              int order, int epf_pass, hipStream_t stream);
 

@@ -957,13 +957,15 @@ constexpr int kPredThreads = 1024;
 constexpr int kGroupBlocks = 32;  // 256 samples (6.2)
 constexpr int kCellLd = 2 * kGroupBlocks + 4;
 
-// One workgroup per group and channel.
-__global__ __launch_bounds__(kPredThreads) void acpred_kernel(PredArgs a, int groups_x) {
+// One workgroup per group and channel: workgroup blk takes channel blk % 3
+// of group blk / 3.
+__device__ __attribute__((always_inline)) inline void acpred_group(const PredArgs& a, int blk,
+                                                                   int groups_x) {
   __shared__ float s_gdc[kGroupBlocks + 2][kGroupBlocks + 2];
   __shared__ float s_cell[kCellLd][kCellLd];
   __shared__ float s_u[3][8][4], s_v[3][8][8];
   const int tid = threadIdx.x;
-  const int c = blockIdx.x % 3, g = blockIdx.x / 3;
+  const int c = blk % 3, g = blk / 3;
   const int gx0 = kGroupBlocks * (g % groups_x), gy0 = kGroupBlocks * (g / groups_x);
   const int gw = min(kGroupBlocks, a.Wb - gx0), gh = min(kGroupBlocks, a.Hb - gy0);
   const DeviceTables* __restrict__ T = a.tab;
@@ -2164,8 +2166,8 @@ struct PatchArgs {
   int* status;
 };
 
-__global__ __launch_bounds__(256) void patches_kernel(PatchArgs a) {
-  const int32_t* q = a.place + 5 * size_t(blockIdx.x);
+__device__ __attribute__((always_inline)) inline void patch_place(const PatchArgs& a, int k) {
+  const int32_t* q = a.place + 5 * size_t(k);
   const int x0 = q[0], y0 = q[1], xs = q[2], ys = q[3], off = q[4];
   const bool ok = xs >= 1 && ys >= 1 && xs <= 16 && ys <= 16 && x0 >= 0 && y0 >= 0 &&
                   x0 <= a.W - xs && y0 <= a.H - ys && off >= 0 &&
@@ -2199,8 +2201,10 @@ struct GabArgs {
   float k0[3], k1[3], k2[3];
 };
 
-__global__ __launch_bounds__(256) void gaborish_kernel(GabArgs a) {
-  const int x = blockIdx.x * 64 + (threadIdx.x & 63), y = blockIdx.y * 4 + (threadIdx.x >> 6);
+// Workgroup (gx, gy): 64 x 4 pixels.
+__device__ __attribute__((always_inline)) inline void gaborish_block(const GabArgs& a, int gx,
+                                                                     int gy) {
+  const int x = gx * 64 + (threadIdx.x & 63), y = gy * 4 + (threadIdx.x >> 6);
   if (x >= a.W || y >= a.H) return;
   const int xl = mirror(x - 1, a.W), xr = mirror(x + 1, a.W);
   const int yu = mirror(y - 1, a.H), yd = mirror(y + 1, a.H);
@@ -2231,8 +2235,8 @@ __device__ inline float lin_dequant(float x, float lo, float hi, float levels) {
   return fmaf((hi - lo) / levels, x + 0.5f, lo);
 }
 
-__global__ __launch_bounds__(256) void dots_kernel(DotArgs a) {
-  const int t = blockIdx.x * 256 + threadIdx.x;
+__device__ __attribute__((always_inline)) inline void dots_block(const DotArgs& a, int blk) {
+  const int t = blk * 256 + threadIdx.x;
   const int k = t / 25, w = t - 25 * k;
   if (k >= a.n) return;
   const int32_t* q = a.dots + 10 * size_t(k);
@@ -2315,12 +2319,12 @@ __device__ inline void spline_ext(const int32_t* q, int n, int e, double& x, dou
   }
 }
 
-__global__ __launch_bounds__(kSplineThreads) void spline_kernel(SplineArgs a) {
+__device__ __attribute__((always_inline)) inline void spline_one(const SplineArgs& a, int sp) {
   __shared__ double s_scan[kSplineThreads];
   __shared__ double s_dct[4][32];
   __shared__ double s_pt[7][kSplineThreads];  // x, y, d sigma / 4, sigma, X, Y, B
   __shared__ int s_bad;
-  const int sp = blockIdx.x, tid = threadIdx.x;
+  const int tid = threadIdx.x;
   const int o0 = a.offsets[sp], o1 = a.offsets[sp + 1];
   if (o0 < 0 || o1 > a.total || o1 <= o0) {  // uniform over the group
     if (tid == 0) atomicOr(a.status, 4);
@@ -2729,8 +2733,9 @@ __device__ inline uint64_t splitmix64(uint64_t z) {
   return z ^ (z >> 31);
 }
 
-__global__ __launch_bounds__(kNoiseThreads) void noise_kernel(NoiseArgs a, int groups_x) {
-  const int c = blockIdx.x % 3, g = blockIdx.x / 3;
+__device__ __attribute__((always_inline)) inline void noise_group(const NoiseArgs& a, int blk,
+                                                                  int groups_x) {
+  const int c = blk % 3, g = blk / 3;
   const int x0 = 256 * (g % groups_x), y0 = 256 * (g / groups_x);
   const int gw = min(256, a.W - x0), gh = min(256, a.H - y0);
   const int lane = threadIdx.x & 7, r0 = kNoiseRows * (threadIdx.x >> 3);
@@ -2826,6 +2831,20 @@ __global__ __launch_bounds__(fin_threads<kFinRowsFrame>()) void finish_kernel(Fi
   const int t = xcd_tile(blockIdx.x, gridDim.x);
   finish_tile<kFinRowsFrame, NOISE>(a, t % tiles_x, t / tiles_x);
 }
+__global__ __launch_bounds__(kPredThreads) void acpred_kernel(PredArgs a, int groups_x) {
+  acpred_group(a, blockIdx.x, groups_x);
+}
+__global__ __launch_bounds__(256) void patches_kernel(PatchArgs a) { patch_place(a, blockIdx.x); }
+__global__ __launch_bounds__(256) void gaborish_kernel(GabArgs a) {
+  gaborish_block(a, blockIdx.x, blockIdx.y);
+}
+__global__ __launch_bounds__(256) void dots_kernel(DotArgs a) { dots_block(a, blockIdx.x); }
+__global__ __launch_bounds__(kSplineThreads) void spline_kernel(SplineArgs a) {
+  spline_one(a, blockIdx.x);
+}
+__global__ __launch_bounds__(kNoiseThreads) void noise_kernel(NoiseArgs a, int groups_x) {
+  noise_group(a, blockIdx.x, groups_x);
+}
 
 // The batch kernels share one tile list over reconstruction, EPF and finish.
 static_assert(kRecTW == kEpfTW && kRecTH == kEpfTH && kRecTW == 64 && kRecTH == 32,
@@ -2835,9 +2854,8 @@ static_assert(kRecTW == kEpfTW && kRecTH == kEpfTH && kRecTW == 64 && kRecTH == 
 struct FrameDesc {
   InfoArgs info;
   ReconArgs rec;
-  EpfArgs epf[2];  // even passes read xyb[0] and write xyb[1]; odd passes the reverse
-  FinishArgs fin;  // reads the XYB buffer the last EPF pass wrote
-  float* xyb[2];
+  EpfArgs epf[3];  // pass k's buffers, as the single-frame decode uses them
+  FinishArgs fin;  // reads the XYB buffer the last stage before it wrote
   int epf_iters;
   int tiles_x;     // 64x32 tiles per row
 };
@@ -2935,7 +2953,7 @@ __global__ __launch_bounds__(kEpfThreads, kEpfMinBlocks) void epf_batch_kernel(B
       static_assert(sizeof(EpfArgs) % 4 == 0, "word copy");
       if (threadIdx.x < sizeof(EpfArgs) / 4)
         reinterpret_cast<uint32_t*>(&s_args)[threadIdx.x] =
-            reinterpret_cast<const uint32_t*>(&d->epf[b.pass & 1])[threadIdx.x];
+            reinterpret_cast<const uint32_t*>(&d->epf[b.pass])[threadIdx.x];
       __syncthreads();
       epf_tile(s_args, lt % tx, lt / tx);
     }
@@ -2943,7 +2961,9 @@ __global__ __launch_bounds__(kEpfThreads, kEpfMinBlocks) void epf_batch_kernel(B
   }
 }
 
-template <bool PERSIST>
+// NOISE: some frame of the batch adds noise; each tile takes the form of
+// its own frame.
+template <bool PERSIST, bool NOISE>
 __global__ __launch_bounds__(fin_threads<kFinRowsBatch>()) void finish_batch_kernel(BatchArgs b) {
   for (TileRange r(b.order, b.tile_start[b.n]); r.t < r.end; r.t += r.step) {
     if (PERSIST) __syncthreads();
@@ -2952,9 +2972,95 @@ __global__ __launch_bounds__(fin_threads<kFinRowsBatch>()) void finish_batch_ker
     const int lt = __builtin_amdgcn_readfirstlane(r.t - b.tile_start[f]);
     const int tx = const_load(&d->tiles_x);
     const FinishArgs a = const_load(&d->fin);
-    finish_tile<kFinRowsBatch>(a, lt % tx, lt / tx);
+    if (NOISE && a.noise)
+      finish_tile<kFinRowsBatch, true>(a, lt % tx, lt / tx);
+    else
+      finish_tile<kFinRowsBatch>(a, lt % tx, lt / tx);
     if (!PERSIST) break;
   }
+}
+
+// Option stages of a batch (AC prediction, quantization constraint,
+// patches, noise, Gaborish before dots and splines, dots, splines): one
+// launch per stage over the workgroups of the frames that take it, one
+// workgroup per unit of the single-frame kernel.  The stage's table holds,
+// per such frame, its arguments and the number of units in a row (groups
+// or tiles); a workgroup finds its frame by binary search over the prefix
+// of unit counts.
+template <typename Args>
+struct OptEntry {
+  Args a;
+  int row;  // units per row: prediction and noise groups, constraint tiles, Gaborish blocks
+};
+
+struct OptBatch {
+  const void* entries;
+  const int* __restrict__ start;  // m + 1 prefix offsets of units
+  int m;
+};
+
+template <typename Args>
+__device__ inline int opt_unit(const OptBatch& ob, Args& a, int& row) {
+  const int k = __builtin_amdgcn_readfirstlane(find_frame(ob.start, ob.m, blockIdx.x));
+  const OptEntry<Args>* e = static_cast<const OptEntry<Args>*>(ob.entries) + k;
+  a = const_load(&e->a);
+  row = const_load(&e->row);
+  return __builtin_amdgcn_readfirstlane(int(blockIdx.x) - ob.start[k]);
+}
+
+// The same with the arguments staged in LDS: structures whose plane
+// pointers the body indexes by channel would otherwise be copied to
+// scratch memory.
+template <typename Args>
+__device__ inline int opt_unit_lds(const OptBatch& ob, Args& s_args, int& row) {
+  const int k = __builtin_amdgcn_readfirstlane(find_frame(ob.start, ob.m, blockIdx.x));
+  const OptEntry<Args>* e = static_cast<const OptEntry<Args>*>(ob.entries) + k;
+  static_assert(sizeof(Args) % 4 == 0, "word copy");
+  for (unsigned i = threadIdx.x; i < sizeof(Args) / 4; i += blockDim.x)
+    reinterpret_cast<uint32_t*>(&s_args)[i] = reinterpret_cast<const uint32_t*>(&e->a)[i];
+  row = const_load(&e->row);
+  __syncthreads();
+  return __builtin_amdgcn_readfirstlane(int(blockIdx.x) - ob.start[k]);
+}
+
+__global__ __launch_bounds__(kPredThreads) void acpred_batch_kernel(OptBatch ob) {
+  __shared__ PredArgs s_args;
+  int row;
+  const int u = opt_unit_lds(ob, s_args, row);
+  acpred_group(s_args, u, row);
+}
+__global__ __launch_bounds__(kRecThreads, 4) void qco_batch_kernel(OptBatch ob) {
+  __shared__ QcoArgs s_args;
+  int row;
+  const int u = opt_unit_lds(ob, s_args, row);
+  qco_tile(s_args, u % row, u / row);
+}
+__global__ __launch_bounds__(256) void patches_batch_kernel(OptBatch ob) {
+  PatchArgs a;
+  int row;
+  patch_place(a, opt_unit(ob, a, row));
+}
+__global__ __launch_bounds__(kNoiseThreads) void noise_batch_kernel(OptBatch ob) {
+  NoiseArgs a;
+  int row;
+  const int u = opt_unit(ob, a, row);
+  noise_group(a, u, row);
+}
+__global__ __launch_bounds__(256) void gaborish_batch_kernel(OptBatch ob) {
+  GabArgs a;
+  int row;
+  const int u = opt_unit(ob, a, row);
+  gaborish_block(a, u % row, u / row);
+}
+__global__ __launch_bounds__(256) void dots_batch_kernel(OptBatch ob) {
+  DotArgs a;
+  int row;
+  dots_block(a, opt_unit(ob, a, row));
+}
+__global__ __launch_bounds__(kSplineThreads) void spline_batch_kernel(OptBatch ob) {
+  SplineArgs a;
+  int row;
+  spline_one(a, opt_unit(ob, a, row));
 }
 
 // ---------------------------------------------------------------------------
@@ -3230,14 +3336,66 @@ size_t pred_bytes(const jxlr_frame_params* p) {
                                      blocks_of(p->ysize))
                           : 0;
 }
+
+// A decode's planes in its workspace, and the XYB buffer each stage reads
+// and writes; the single-frame decode and every frame of a batch use this
+// one layout.  EPF passes alternate between buf[0] and buf[1]; with the
+// quantization constraint, passes after the first one write buf[2] and
+// buf[1] in turn, so the reconstruction in buf[0] stays for the constraint.
+struct FrameBuffers {
+  uint8_t* info;
+  float* buf[3];
+  float* pred;    // Annex H sums, or null
+  float* noise;   // K.5 channels, or null
+  float* gab;     // Gaborish before dots and splines, or null
+  void* spline;   // K.4 curve samples, or null
+  const float* epf_in[3];
+  float* epf_out[3];
+  float* post;    // after the EPF passes and the constraint; patches go here
+  float* fin;     // what the finish reads: post, or gab
+};
+
+// Bytes of the layout frame_buffers lays out.
+size_t frame_ws_bytes(const jxlr_frame_params* p) {
+  return info_bytes(p) + xyb_buffers(p) * xyb_bytes(p) + pred_bytes(p) +
+         (p->noise ? xyb_bytes(p) : 0) + (gab_pass(p) ? xyb_bytes(p) : 0) + spline_bytes(p);
+}
+
+FrameBuffers frame_buffers(const jxlr_frame_params* p, char* base) {
+  FrameBuffers b{};
+  b.info = reinterpret_cast<uint8_t*>(base);
+  char* t = base + info_bytes(p);
+  for (int i = 0; i < xyb_buffers(p); ++i, t += xyb_bytes(p)) b.buf[i] = reinterpret_cast<float*>(t);
+  if (p->ac_prediction) b.pred = reinterpret_cast<float*>(t);
+  t += pred_bytes(p);
+  if (p->noise) {
+    b.noise = reinterpret_cast<float*>(t);
+    t += xyb_bytes(p);
+  }
+  if (gab_pass(p)) {
+    b.gab = reinterpret_cast<float*>(t);
+    t += xyb_bytes(p);
+  }
+  if (p->num_splines > 0) b.spline = t;
+  const bool qco = p->qco && p->epf_iters > 0;
+  float* cur = b.buf[0];
+  for (int it = 0; it < p->epf_iters; ++it) {
+    float* dst = (it & 1) ? (qco ? b.buf[2] : b.buf[0]) : b.buf[1];
+    b.epf_in[it] = cur;
+    b.epf_out[it] = dst;
+    cur = dst;
+  }
+  b.post = cur;
+  b.fin = b.gab ? b.gab : cur;
+  return b;
+}
 }  // namespace
 
 extern "C" {
 
 size_t jxlr_workspace_bytes(const jxlr_frame_params* p) {
   if (check_params(p) != JXLR_OK) return 0;
-  return info_bytes(p) + xyb_buffers(p) * xyb_bytes(p) + pred_bytes(p) +
-         (p->noise ? xyb_bytes(p) : 0) + (gab_pass(p) ? xyb_bytes(p) : 0) + spline_bytes(p);
+  return frame_ws_bytes(p);
 }
 
 size_t jxlr_spline_scratch_bytes(const jxlr_frame_params* p) {
@@ -3465,8 +3623,16 @@ jxlr_status jxlr_epf_pass(jxlr_ctx* ctx, const jxlr_frame_params* p, const jxlr_
   return launch_status(hipGetLastError());
 }
 
-jxlr_status jxlr_ac_prediction(jxlr_ctx* ctx, const jxlr_frame_params* p, const jxlr_frame_io* io,
-                               const uint8_t* info, float* pred, hipStream_t stream) {
+}  // extern "C"
+
+namespace {
+
+// Argument builders of the option stages, shared by their single-frame entry
+// points and the batch.  *row receives the units per row of the launch
+// (groups, tiles or 64x4 blocks) and *units the workgroup count.
+
+jxlr_status make_pred_args(jxlr_ctx* ctx, const jxlr_frame_params* p, const jxlr_frame_io* io,
+                           const uint8_t* info, float* pred, PredArgs* out, int* row, int* units) {
   if (!ctx || !info || !pred || !io) return JXLR_E_NULL;
   jxlr_status st = check_params(p);
   if (st) return st;
@@ -3493,40 +3659,38 @@ jxlr_status jxlr_ac_prediction(jxlr_ctx* ctx, const jxlr_frame_params* p, const 
   a.pred = pred;
   a.tab = ctx->tables;
   const int gx = (Wb + kGroupBlocks - 1) / kGroupBlocks, gy = (Hb + kGroupBlocks - 1) / kGroupBlocks;
-  DeviceGuard g(ctx->device);
-  if (!g.ok) return JXLR_E_HIP;
-  hipLaunchKernelGGL(acpred_kernel, dim3(3 * gx * gy), dim3(kPredThreads), 0, stream, a, gx);
-  return launch_status(hipGetLastError());
+  *out = a;
+  *row = gx;
+  *units = 3 * gx * gy;
+  return JXLR_OK;
 }
 
-jxlr_status jxlr_patches(jxlr_ctx* ctx, const jxlr_frame_params* p, const jxlr_frame_io* io,
-                         float* xyb, size_t stride, hipStream_t stream) {
+jxlr_status make_patch_args(jxlr_ctx* ctx, const jxlr_frame_params* p, const jxlr_frame_io* io,
+                            float* xyb, size_t stride, PatchArgs* out, int* units) {
   if (!ctx || !io || !xyb) return JXLR_E_NULL;
   jxlr_status st = check_params(p);
   if (st) return st;
   if (stride < p->xsize) return JXLR_E_SIZE;
+  *units = p->num_patches;
   if (p->num_patches == 0) return JXLR_OK;
   if (!io->patch_place || !io->patch_samples) return JXLR_E_NULL;
-  PatchArgs a{int(p->xsize), int(p->ysize), xyb, stride, io->patch_place, io->patch_samples,
-              io->patch_samples_count, ctx->status};
-  DeviceGuard g(ctx->device);
-  if (!g.ok) return JXLR_E_HIP;
-  hipLaunchKernelGGL(patches_kernel, dim3(p->num_patches), dim3(256), 0, stream, a);
-  return launch_status(hipGetLastError());
+  *out = PatchArgs{int(p->xsize), int(p->ysize), xyb, stride, io->patch_place, io->patch_samples,
+                   io->patch_samples_count, ctx->status};
+  return JXLR_OK;
 }
 
-jxlr_status jxlr_gaborish(jxlr_ctx* ctx, const jxlr_frame_params* p, const float* in, float* out,
-                          size_t stride, hipStream_t stream) {
-  if (!ctx || !in || !out) return JXLR_E_NULL;
+jxlr_status make_gab_args(jxlr_ctx* ctx, const jxlr_frame_params* p, const float* in, float* outp,
+                          size_t stride, GabArgs* out, int* row, int* units) {
+  if (!ctx || !in || !outp) return JXLR_E_NULL;
   jxlr_status st = check_params(p);
   if (st) return st;
   if (stride < p->xsize) return JXLR_E_SIZE;
-  if (in == out) return JXLR_E_PARAM;
+  if (in == outp) return JXLR_E_PARAM;
   GabArgs a{};
   a.W = int(p->xsize);
   a.H = int(p->ysize);
   a.in = in;
-  a.out = out;
+  a.out = outp;
   a.stride = stride;
   for (int c = 0; c < 3; ++c) {
     const double w1 = p->gab_w1[c], w2 = p->gab_w2[c];
@@ -3535,66 +3699,63 @@ jxlr_status jxlr_gaborish(jxlr_ctx* ctx, const jxlr_frame_params* p, const float
     a.k1[c] = float(w1 / norm);
     a.k2[c] = float(w2 / norm);
   }
-  DeviceGuard g(ctx->device);
-  if (!g.ok) return JXLR_E_HIP;
-  hipLaunchKernelGGL(gaborish_kernel, dim3((p->xsize + 63) / 64, (p->ysize + 3) / 4), dim3(256), 0,
-                     stream, a);
-  return launch_status(hipGetLastError());
+  *out = a;
+  *row = int((p->xsize + 63) / 64);
+  *units = *row * int((p->ysize + 3) / 4);
+  return JXLR_OK;
 }
 
-jxlr_status jxlr_dots(jxlr_ctx* ctx, const jxlr_frame_params* p, const jxlr_frame_io* io,
-                      float* xyb, size_t stride, hipStream_t stream) {
+jxlr_status make_dot_args(jxlr_ctx* ctx, const jxlr_frame_params* p, const jxlr_frame_io* io,
+                          float* xyb, size_t stride, DotArgs* out, int* units) {
   if (!ctx || !io || !xyb) return JXLR_E_NULL;
   jxlr_status st = check_params(p);
   if (st) return st;
   if (stride < p->xsize) return JXLR_E_SIZE;
+  *units = 0;
   if (p->num_dots == 0) return JXLR_OK;
   if (!io->dots) return JXLR_E_NULL;
+  const long long threads = 25LL * p->num_dots;
+  if ((threads + 255) / 256 > INT32_MAX / 2) return JXLR_E_SIZE;
   DotArgs a{int(p->xsize), int(p->ysize), xyb, stride, io->dots, p->num_dots, {}};
   for (int c = 0; c < 3; ++c) a.colour_quant[c] = p->dot_colour_quant[c];
-  const long long threads = 25LL * p->num_dots;
-  DeviceGuard g(ctx->device);
-  if (!g.ok) return JXLR_E_HIP;
-  hipLaunchKernelGGL(dots_kernel, dim3(unsigned((threads + 255) / 256)), dim3(256), 0, stream, a);
-  return launch_status(hipGetLastError());
+  *out = a;
+  *units = int((threads + 255) / 256);
+  return JXLR_OK;
 }
 
-jxlr_status jxlr_splines(jxlr_ctx* ctx, const jxlr_frame_params* p, const jxlr_frame_io* io,
-                         float* xyb, size_t stride, void* scratch, size_t scratch_bytes,
-                         hipStream_t stream) {
+jxlr_status make_spline_args(jxlr_ctx* ctx, const jxlr_frame_params* p, const jxlr_frame_io* io,
+                             float* xyb, size_t stride, void* scratch, size_t scratch_bytes,
+                             SplineArgs* out, int* units) {
   if (!ctx || !io || !xyb) return JXLR_E_NULL;
   jxlr_status st = check_params(p);
   if (st) return st;
   if (stride < p->xsize) return JXLR_E_SIZE;
+  *units = p->num_splines;
   if (p->num_splines == 0) return JXLR_OK;
   if (!io->spline_offsets || !io->spline_points || !io->spline_dct || !scratch)
     return JXLR_E_NULL;
   if (scratch_bytes < spline_bytes(p)) return JXLR_E_WORKSPACE;
-  SplineArgs a{int(p->xsize), int(p->ysize), xyb, stride, io->spline_offsets, io->spline_points,
-               io->spline_dct, p->num_splines, p->num_spline_points,
-               static_cast<double*>(scratch), ctx->status, ctx->tables};
-  DeviceGuard g(ctx->device);
-  if (!g.ok) return JXLR_E_HIP;
-  hipLaunchKernelGGL(spline_kernel, dim3(p->num_splines), dim3(kSplineThreads), 0, stream, a);
-  return launch_status(hipGetLastError());
+  *out = SplineArgs{int(p->xsize), int(p->ysize), xyb, stride, io->spline_offsets,
+                    io->spline_points, io->spline_dct, p->num_splines, p->num_spline_points,
+                    static_cast<double*>(scratch), ctx->status, ctx->tables};
+  return JXLR_OK;
 }
 
-jxlr_status jxlr_noise_channels(jxlr_ctx* ctx, const jxlr_frame_params* p, float* raw,
-                                hipStream_t stream) {
+jxlr_status make_noise_args(jxlr_ctx* ctx, const jxlr_frame_params* p, float* raw,
+                            NoiseArgs* out, int* row, int* units) {
   if (!ctx || !raw) return JXLR_E_NULL;
   jxlr_status st = check_params(p);
   if (st) return st;
-  NoiseArgs a{int(p->xsize), int(p->ysize), raw, ctx->tables};
+  *out = NoiseArgs{int(p->xsize), int(p->ysize), raw, ctx->tables};
   const int gx = int((p->xsize + 255) / 256), gy = int((p->ysize + 255) / 256);
-  DeviceGuard g(ctx->device);
-  if (!g.ok) return JXLR_E_HIP;
-  hipLaunchKernelGGL(noise_kernel, dim3(3 * gx * gy), dim3(kNoiseThreads), 0, stream, a, gx);
-  return launch_status(hipGetLastError());
+  *row = gx;
+  *units = 3 * gx * gy;
+  return JXLR_OK;
 }
 
-jxlr_status jxlr_qco_pass(jxlr_ctx* ctx, const jxlr_frame_params* p, const jxlr_frame_io* io,
+jxlr_status make_qco_args(jxlr_ctx* ctx, const jxlr_frame_params* p, const jxlr_frame_io* io,
                           const uint8_t* info, const float* orig, float* xyb_io, size_t stride,
-                          hipStream_t stream) {
+                          QcoArgs* out, int* row, int* units) {
   if (!ctx || !info || !orig || !xyb_io) return JXLR_E_NULL;
   jxlr_status st = check_params(p);
   if (st) return st;
@@ -3626,10 +3787,99 @@ jxlr_status jxlr_qco_pass(jxlr_ctx* ctx, const jxlr_frame_params* p, const jxlr_
   a.vec = (stride & 3) == 0 && (size_t(p->ysize) * stride & 3) == 0 &&
           (reinterpret_cast<uintptr_t>(orig) & 15) == 0 &&
           (reinterpret_cast<uintptr_t>(xyb_io) & 15) == 0;
+  *out = a;
+  *row = tiles_x(p);
+  *units = tiles_x(p) * tiles_y(p);
+  return JXLR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+jxlr_status jxlr_ac_prediction(jxlr_ctx* ctx, const jxlr_frame_params* p, const jxlr_frame_io* io,
+                               const uint8_t* info, float* pred, hipStream_t stream) {
+  PredArgs a;
+  int gx, units;
+  jxlr_status st = make_pred_args(ctx, p, io, info, pred, &a, &gx, &units);
+  if (st) return st;
   DeviceGuard g(ctx->device);
   if (!g.ok) return JXLR_E_HIP;
-  hipLaunchKernelGGL(qco_kernel, dim3(tiles_x(p) * tiles_y(p)), dim3(kRecThreads), 0, stream, a,
-                     tiles_x(p));
+  hipLaunchKernelGGL(acpred_kernel, dim3(units), dim3(kPredThreads), 0, stream, a, gx);
+  return launch_status(hipGetLastError());
+}
+
+jxlr_status jxlr_patches(jxlr_ctx* ctx, const jxlr_frame_params* p, const jxlr_frame_io* io,
+                         float* xyb, size_t stride, hipStream_t stream) {
+  PatchArgs a;
+  int units;
+  jxlr_status st = make_patch_args(ctx, p, io, xyb, stride, &a, &units);
+  if (st || units == 0) return st;
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return JXLR_E_HIP;
+  hipLaunchKernelGGL(patches_kernel, dim3(units), dim3(256), 0, stream, a);
+  return launch_status(hipGetLastError());
+}
+
+jxlr_status jxlr_gaborish(jxlr_ctx* ctx, const jxlr_frame_params* p, const float* in, float* out,
+                          size_t stride, hipStream_t stream) {
+  GabArgs a;
+  int gx, units;
+  jxlr_status st = make_gab_args(ctx, p, in, out, stride, &a, &gx, &units);
+  if (st) return st;
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return JXLR_E_HIP;
+  hipLaunchKernelGGL(gaborish_kernel, dim3(gx, units / gx), dim3(256), 0, stream, a);
+  return launch_status(hipGetLastError());
+}
+
+jxlr_status jxlr_dots(jxlr_ctx* ctx, const jxlr_frame_params* p, const jxlr_frame_io* io,
+                      float* xyb, size_t stride, hipStream_t stream) {
+  DotArgs a;
+  int units;
+  jxlr_status st = make_dot_args(ctx, p, io, xyb, stride, &a, &units);
+  if (st || units == 0) return st;
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return JXLR_E_HIP;
+  hipLaunchKernelGGL(dots_kernel, dim3(units), dim3(256), 0, stream, a);
+  return launch_status(hipGetLastError());
+}
+
+jxlr_status jxlr_splines(jxlr_ctx* ctx, const jxlr_frame_params* p, const jxlr_frame_io* io,
+                         float* xyb, size_t stride, void* scratch, size_t scratch_bytes,
+                         hipStream_t stream) {
+  SplineArgs a;
+  int units;
+  jxlr_status st = make_spline_args(ctx, p, io, xyb, stride, scratch, scratch_bytes, &a, &units);
+  if (st || units == 0) return st;
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return JXLR_E_HIP;
+  hipLaunchKernelGGL(spline_kernel, dim3(units), dim3(kSplineThreads), 0, stream, a);
+  return launch_status(hipGetLastError());
+}
+
+jxlr_status jxlr_noise_channels(jxlr_ctx* ctx, const jxlr_frame_params* p, float* raw,
+                                hipStream_t stream) {
+  NoiseArgs a;
+  int gx, units;
+  jxlr_status st = make_noise_args(ctx, p, raw, &a, &gx, &units);
+  if (st) return st;
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return JXLR_E_HIP;
+  hipLaunchKernelGGL(noise_kernel, dim3(units), dim3(kNoiseThreads), 0, stream, a, gx);
+  return launch_status(hipGetLastError());
+}
+
+jxlr_status jxlr_qco_pass(jxlr_ctx* ctx, const jxlr_frame_params* p, const jxlr_frame_io* io,
+                          const uint8_t* info, const float* orig, float* xyb_io, size_t stride,
+                          hipStream_t stream) {
+  QcoArgs a;
+  int tx, units;
+  jxlr_status st = make_qco_args(ctx, p, io, info, orig, xyb_io, stride, &a, &tx, &units);
+  if (st) return st;
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return JXLR_E_HIP;
+  hipLaunchKernelGGL(qco_kernel, dim3(units), dim3(kRecThreads), 0, stream, a, tx);
   return launch_status(hipGetLastError());
 }
 
@@ -3657,54 +3907,31 @@ jxlr_status jxlr_decode(jxlr_ctx* ctx, const jxlr_frame_params* p, const jxlr_fr
   if (st) return st;
   const size_t need = jxlr_workspace_bytes(p);
   if (ws_bytes < need) return JXLR_E_WORKSPACE;
-  char* base = static_cast<char*>(ws);
-  uint8_t* info = reinterpret_cast<uint8_t*>(base);
-  float* buf[3];
-  for (int i = 0; i < 3; ++i)
-    buf[i] = reinterpret_cast<float*>(base + info_bytes(p) + size_t(i) * xyb_bytes(p));
+  const FrameBuffers b = frame_buffers(p, static_cast<char*>(ws));
   const size_t stride = p->xsize;
   jxlr_frame_io iop = *io;
-  if ((st = jxlr_block_info(ctx, p, io, info, stream))) return st;
-  if (p->ac_prediction) {
-    float* pred = reinterpret_cast<float*>(base + info_bytes(p) + xyb_buffers(p) * xyb_bytes(p));
-    if ((st = jxlr_ac_prediction(ctx, p, io, info, pred, stream))) return st;
-    iop.ac_pred = pred;
-  }
-  if ((st = jxlr_reconstruct(ctx, p, &iop, info, buf[0], stride, stream))) return st;
-  // the passes alternate between two buffers; with the quantization
-  // constraint the reconstruction in buf[0] stays untouched
-  const bool qco = p->qco && p->epf_iters > 0;
-  float* cur = buf[0];
-  for (int it = 0; it < p->epf_iters; ++it) {
-    float* dst = (it & 1) ? (qco ? buf[2] : buf[0]) : buf[1];
-    if ((st = jxlr_epf_pass(ctx, p, io, info, cur, dst, stride, nullptr, nullptr, stream)))
+  iop.ac_pred = b.pred;
+  iop.noise_raw = b.noise;
+  if ((st = jxlr_block_info(ctx, p, io, b.info, stream))) return st;
+  if (p->ac_prediction && (st = jxlr_ac_prediction(ctx, p, io, b.info, b.pred, stream))) return st;
+  if ((st = jxlr_reconstruct(ctx, p, &iop, b.info, b.buf[0], stride, stream))) return st;
+  for (int it = 0; it < p->epf_iters; ++it)
+    if ((st = jxlr_epf_pass(ctx, p, io, b.info, b.epf_in[it], b.epf_out[it], stride, nullptr,
+                            nullptr, stream)))
       return st;
-    cur = dst;
-  }
-  if (qco && (st = jxlr_qco_pass(ctx, p, io, info, buf[0], cur, stride, stream))) return st;
-  if (p->num_patches > 0 && (st = jxlr_patches(ctx, p, io, cur, stride, stream))) return st;
-  char* tail = base + info_bytes(p) + xyb_buffers(p) * xyb_bytes(p) + pred_bytes(p);
-  if (p->noise) {
-    float* raw = reinterpret_cast<float*>(tail);
-    tail += xyb_bytes(p);
-    if ((st = jxlr_noise_channels(ctx, p, raw, stream))) return st;
-    iop.noise_raw = raw;
-  }
-  if (p->num_dots > 0 || p->num_splines > 0) {
-    // K.1: Gaborish, then the dots and the splines; the finish then skips
-    // its Gaborish
-    if (gab_pass(p)) {
-      float* gab = reinterpret_cast<float*>(tail);
-      tail += xyb_bytes(p);
-      if ((st = jxlr_gaborish(ctx, p, cur, gab, stride, stream))) return st;
-      cur = gab;
-    }
-    if (p->num_dots > 0 && (st = jxlr_dots(ctx, p, io, cur, stride, stream))) return st;
-    if (p->num_splines > 0 &&
-        (st = jxlr_splines(ctx, p, io, cur, stride, tail, spline_bytes(p), stream)))
-      return st;
-  }
-  return jxlr_finish(ctx, p, &iop, cur, stride, stream);
+  if (p->qco && p->epf_iters > 0 &&
+      (st = jxlr_qco_pass(ctx, p, io, b.info, b.buf[0], b.post, stride, stream)))
+    return st;
+  if (p->num_patches > 0 && (st = jxlr_patches(ctx, p, io, b.post, stride, stream))) return st;
+  if (p->noise && (st = jxlr_noise_channels(ctx, p, b.noise, stream))) return st;
+  // K.1: Gaborish, then the dots and the splines; the finish then skips its
+  // Gaborish
+  if (b.gab && (st = jxlr_gaborish(ctx, p, b.post, b.gab, stride, stream))) return st;
+  if (p->num_dots > 0 && (st = jxlr_dots(ctx, p, io, b.fin, stride, stream))) return st;
+  if (p->num_splines > 0 &&
+      (st = jxlr_splines(ctx, p, io, b.fin, stride, b.spline, spline_bytes(p), stream)))
+    return st;
+  return jxlr_finish(ctx, p, &iop, b.fin, stride, stream);
 }
 
 jxlr_status jxlr_decode_noalloc(jxlr_ctx* ctx, const jxlr_frame_params* p,
@@ -3916,9 +4143,45 @@ jxlr_status jxlr_jpeg1_decode(jxlr_ctx* ctx, const jxlr_jpeg1_params* p,
 // ---- batches ---------------------------------------------------------------
 
 namespace {
+constexpr int kOptStages = JXLR_BATCH_OPT_STAGES;
+static_assert(JXLR_STAGE_SPLINES - JXLR_STAGE_PRED + 1 == kOptStages, "option stage numbering");
+
+// Whether frame p takes option stage k (JXLR_STAGE_PRED + k), as the
+// single-frame decode does.
+bool takes_opt(const jxlr_frame_params* p, int k) {
+  switch (JXLR_STAGE_PRED + k) {
+    case JXLR_STAGE_PRED: return p->ac_prediction != 0;
+    case JXLR_STAGE_QCO: return p->qco && p->epf_iters > 0;
+    case JXLR_STAGE_PATCHES: return p->num_patches > 0;
+    case JXLR_STAGE_NOISE: return p->noise != 0;
+    case JXLR_STAGE_GABORISH: return gab_pass(p);
+    case JXLR_STAGE_DOTS: return p->num_dots > 0;
+    case JXLR_STAGE_SPLINES: return p->num_splines > 0;
+  }
+  return false;
+}
+
+size_t opt_entry_bytes(int k) {
+  switch (JXLR_STAGE_PRED + k) {
+    case JXLR_STAGE_PRED: return sizeof(OptEntry<PredArgs>);
+    case JXLR_STAGE_QCO: return sizeof(OptEntry<QcoArgs>);
+    case JXLR_STAGE_PATCHES: return sizeof(OptEntry<PatchArgs>);
+    case JXLR_STAGE_NOISE: return sizeof(OptEntry<NoiseArgs>);
+    case JXLR_STAGE_GABORISH: return sizeof(OptEntry<GabArgs>);
+    case JXLR_STAGE_DOTS: return sizeof(OptEntry<DotArgs>);
+    case JXLR_STAGE_SPLINES: return sizeof(OptEntry<SplineArgs>);
+  }
+  return 0;
+}
+
+// The workspace of a batch: a header (frame descriptors, the tile and
+// region tables, each option stage's table and unit prefix), then per frame
+// the layout of its single-frame workspace.
 struct BatchLayout {
   size_t frames, tile_frame, tile_start, region_start, header, total;
-  std::vector<size_t> frame_off;  // per frame: info, then XYB buffers
+  size_t opt_entries[kOptStages], opt_start[kOptStages];
+  int opt_frames[kOptStages];
+  std::vector<size_t> frame_off;
 };
 
 BatchLayout batch_layout(int n, const jxlr_frame_params* p) {
@@ -3929,11 +4192,20 @@ BatchLayout batch_layout(int n, const jxlr_frame_params* p) {
   L.tile_frame = round256(sizeof(FrameDesc) * size_t(n));
   L.tile_start = L.tile_frame + round256(sizeof(int) * tiles);
   L.region_start = L.tile_start + round256(sizeof(int) * size_t(n + 1));
-  L.header = L.region_start + round256(sizeof(int) * size_t(n + 1));
-  size_t off = L.header;
+  size_t off = L.region_start + round256(sizeof(int) * size_t(n + 1));
+  for (int k = 0; k < kOptStages; ++k) {
+    int m = 0;
+    for (int i = 0; i < n; ++i) m += takes_opt(&p[i], k);
+    L.opt_frames[k] = m;
+    L.opt_entries[k] = off;
+    off += round256(opt_entry_bytes(k) * size_t(m));
+    L.opt_start[k] = off;
+    off += round256(sizeof(int) * size_t(m + 1));
+  }
+  L.header = off;
   for (int i = 0; i < n; ++i) {
     L.frame_off.push_back(off);
-    off += info_bytes(&p[i]) + (p[i].epf_iters > 0 ? 2 : 1) * xyb_bytes(&p[i]);
+    off += frame_ws_bytes(&p[i]);
   }
   L.total = off;
   return L;
@@ -3944,15 +4216,54 @@ jxlr_status check_plan(jxlr_ctx* ctx, const jxlr_batch_plan* plan) {
   if (plan->n <= 0 || plan->total_tiles <= 0 || plan->total_regions <= 0 ||
       plan->max_epf_iters < 0 || plan->max_epf_iters > 3)
     return JXLR_E_SIZE;
+  for (int k = 0; k < kOptStages; ++k)
+    if (plan->opt_frames[k] < 0 || plan->opt_frames[k] > plan->n || plan->opt_units[k] < 0)
+      return JXLR_E_SIZE;
   return JXLR_OK;
 }
 
-// Enqueues one stage of a prepared batch.  grid <= 0 picks one workgroup per
-// tile (per kInfoThreads regions for the block-info stage); larger grids are
-// clamped to that.
+// Enqueues one stage of a prepared batch.  Tile stages: grid <= 0 picks one
+// workgroup per tile (per kInfoThreads regions for the block-info stage);
+// larger grids are clamped to that.  Option stages take one workgroup per
+// unit and ignore grid and order; a stage no frame takes launches nothing.
 jxlr_status launch_stage(jxlr_ctx* ctx, const jxlr_batch_plan* plan, int stage, int grid,
                          int order, int epf_pass, hipStream_t stream) {
   char* base = static_cast<char*>(plan->ws);
+  (void)ctx;
+  if (stage >= JXLR_STAGE_PRED) {
+    const int k = stage - JXLR_STAGE_PRED;
+    if (plan->opt_frames[k] == 0 || plan->opt_units[k] == 0) return JXLR_OK;
+    const OptBatch ob{base + plan->opt_entries_offset[k],
+                      reinterpret_cast<const int*>(base + plan->opt_start_offset[k]),
+                      plan->opt_frames[k]};
+    const dim3 g(plan->opt_units[k]);
+    switch (stage) {
+      case JXLR_STAGE_PRED:
+        hipLaunchKernelGGL(acpred_batch_kernel, g, dim3(kPredThreads), 0, stream, ob);
+        break;
+      case JXLR_STAGE_QCO:
+        hipLaunchKernelGGL(qco_batch_kernel, g, dim3(kRecThreads), 0, stream, ob);
+        break;
+      case JXLR_STAGE_PATCHES:
+        hipLaunchKernelGGL(patches_batch_kernel, g, dim3(256), 0, stream, ob);
+        break;
+      case JXLR_STAGE_NOISE:
+        hipLaunchKernelGGL(noise_batch_kernel, g, dim3(kNoiseThreads), 0, stream, ob);
+        break;
+      case JXLR_STAGE_GABORISH:
+        hipLaunchKernelGGL(gaborish_batch_kernel, g, dim3(256), 0, stream, ob);
+        break;
+      case JXLR_STAGE_DOTS:
+        hipLaunchKernelGGL(dots_batch_kernel, g, dim3(256), 0, stream, ob);
+        break;
+      case JXLR_STAGE_SPLINES:
+        hipLaunchKernelGGL(spline_batch_kernel, g, dim3(kSplineThreads), 0, stream, ob);
+        break;
+      default:
+        return JXLR_E_PARAM;
+    }
+    return launch_status(hipGetLastError());
+  }
   BatchArgs b;
   b.frames = reinterpret_cast<const FrameDesc*>(base + plan->frames_offset);
   b.tile_frame = reinterpret_cast<const int*>(base + plan->tile_frame_offset);
@@ -3964,7 +4275,6 @@ jxlr_status launch_stage(jxlr_ctx* ctx, const jxlr_batch_plan* plan, int stage, 
                                             : plan->total_tiles;
   int gsz = grid > 0 ? std::min(grid, full) : full;
   b.order = order == 1 ? 1 : 0;
-  (void)ctx;
   const bool persist = gsz < full;
   switch (stage) {
     case JXLR_STAGE_INFO:
@@ -3983,18 +4293,26 @@ jxlr_status launch_stage(jxlr_ctx* ctx, const jxlr_batch_plan* plan, int stage, 
       else
         hipLaunchKernelGGL(epf_batch_kernel<false>, dim3(gsz), dim3(kEpfThreads), 0, stream, b);
       break;
-    case JXLR_STAGE_FINISH:
-      if (persist)
-        hipLaunchKernelGGL(finish_batch_kernel<true>, dim3(gsz), dim3(fin_threads<kFinRowsBatch>()),
-                           0, stream, b);
-      else
-        hipLaunchKernelGGL(finish_batch_kernel<false>, dim3(gsz), dim3(fin_threads<kFinRowsBatch>()),
-                           0, stream, b);
+    case JXLR_STAGE_FINISH: {
+      const bool nz = plan->any_noise != 0;
+      auto k = persist ? (nz ? finish_batch_kernel<true, true> : finish_batch_kernel<true, false>)
+                       : (nz ? finish_batch_kernel<false, true> : finish_batch_kernel<false, false>);
+      hipLaunchKernelGGL(k, dim3(gsz), dim3(fin_threads<kFinRowsBatch>()), 0, stream, b);
       break;
+    }
     default:
       return JXLR_E_PARAM;
   }
   return launch_status(hipGetLastError());
+}
+
+// Appends frame i's entry for option stage k to the stage's table.
+template <typename Args>
+void put_entry(std::vector<char>& hdr, size_t at, const Args& a, int row) {
+  OptEntry<Args> e{};
+  e.a = a;
+  e.row = row;
+  std::memcpy(hdr.data() + at, &e, sizeof(e));
 }
 }  // namespace
 
@@ -4003,9 +4321,7 @@ extern "C" {
 size_t jxlr_batch_workspace_bytes(int n, const jxlr_frame_params* p) {
   if (n <= 0 || !p) return 0;
   for (int i = 0; i < n; ++i)
-    if (check_params(&p[i]) != JXLR_OK || p[i].qco || p[i].ac_prediction || p[i].noise ||
-        p[i].num_patches || p[i].num_dots || p[i].num_splines)
-      return 0;
+    if (check_params(&p[i]) != JXLR_OK) return 0;
   return batch_layout(n, p).total;
 }
 
@@ -4017,35 +4333,85 @@ jxlr_status jxlr_batch_prepare(jxlr_ctx* ctx, int n, const jxlr_frame_params* p,
   for (int i = 0; i < n; ++i) {
     jxlr_status st = check_params(&p[i]);
     if (st) return st;
-    // the batch stages have no constraint, prediction, patch, dot or noise stage
-    if (p[i].qco || p[i].ac_prediction || p[i].noise || p[i].num_patches || p[i].num_dots ||
-        p[i].num_splines)
-      return JXLR_E_PARAM;
   }
   const BatchLayout L = batch_layout(n, p);
   if (ws_bytes < L.total) return JXLR_E_WORKSPACE;
   char* base = static_cast<char*>(ws);
+  // the header is assembled on the host and copied in one piece
+  std::vector<char> hdr(L.header, 0);
   std::vector<FrameDesc> frames(n);
   std::vector<int> tstart(n + 1, 0), rstart(n + 1, 0), tframe;
-  int max_epf = 0;
+  std::vector<int> ostart[kOptStages];
+  for (int k = 0; k < kOptStages; ++k) ostart[k].push_back(0);
+  int max_epf = 0, any_noise = 0;
   for (int i = 0; i < n; ++i) {
     FrameDesc& d = frames[i];
-    char* fb = base + L.frame_off[i];
-    uint8_t* info = reinterpret_cast<uint8_t*>(fb);
-    d.xyb[0] = reinterpret_cast<float*>(fb + info_bytes(&p[i]));
-    d.xyb[1] = p[i].epf_iters > 0 ? reinterpret_cast<float*>(fb + info_bytes(&p[i]) + xyb_bytes(&p[i]))
-                                  : d.xyb[0];
+    const FrameBuffers fb = frame_buffers(&p[i], base + L.frame_off[i]);
+    jxlr_frame_io iop = io[i];
+    iop.ac_pred = fb.pred;
+    iop.noise_raw = fb.noise;
     const size_t stride = p[i].xsize;
-    jxlr_status st = make_info_args(ctx, &p[i], &io[i], info, &d.info);
-    if (!st) st = make_recon_args(ctx, &p[i], &io[i], info, d.xyb[0], stride, &d.rec);
-    if (!st && p[i].epf_iters > 0)
-      st = make_epf_args(ctx, &p[i], &io[i], info, d.xyb[0], d.xyb[1], stride, nullptr, nullptr,
-                         &d.epf[0]);
-    if (!st && p[i].epf_iters > 1)
-      st = make_epf_args(ctx, &p[i], &io[i], info, d.xyb[1], d.xyb[0], stride, nullptr, nullptr,
-                         &d.epf[1]);
-    if (!st)
-      st = make_finish_args(ctx, &p[i], &io[i], d.xyb[p[i].epf_iters & 1], stride, &d.fin);
+    jxlr_status st = make_info_args(ctx, &p[i], &iop, fb.info, &d.info);
+    if (!st) st = make_recon_args(ctx, &p[i], &iop, fb.info, fb.buf[0], stride, &d.rec);
+    for (int k = 0; k < p[i].epf_iters && !st; ++k)
+      st = make_epf_args(ctx, &p[i], &iop, fb.info, fb.epf_in[k], fb.epf_out[k], stride, nullptr,
+                         nullptr, &d.epf[k]);
+    if (!st) st = make_finish_args(ctx, &p[i], &iop, fb.fin, stride, &d.fin);
+    // option stages, in the order of the single-frame decode
+    for (int k = 0; k < kOptStages && !st; ++k) {
+      if (!takes_opt(&p[i], k)) continue;
+      const size_t at = L.opt_entries[k] + opt_entry_bytes(k) * (ostart[k].size() - 1);
+      int row = 0, units = 0;
+      switch (JXLR_STAGE_PRED + k) {
+        case JXLR_STAGE_PRED: {
+          PredArgs a;
+          if (!(st = make_pred_args(ctx, &p[i], &iop, fb.info, fb.pred, &a, &row, &units)))
+            put_entry(hdr, at, a, row);
+          break;
+        }
+        case JXLR_STAGE_QCO: {
+          QcoArgs a;
+          if (!(st = make_qco_args(ctx, &p[i], &iop, fb.info, fb.buf[0], fb.post, stride, &a, &row,
+                                   &units)))
+            put_entry(hdr, at, a, row);
+          break;
+        }
+        case JXLR_STAGE_PATCHES: {
+          PatchArgs a;
+          if (!(st = make_patch_args(ctx, &p[i], &iop, fb.post, stride, &a, &units)))
+            put_entry(hdr, at, a, 0);
+          break;
+        }
+        case JXLR_STAGE_NOISE: {
+          NoiseArgs a;
+          if (!(st = make_noise_args(ctx, &p[i], fb.noise, &a, &row, &units)))
+            put_entry(hdr, at, a, row);
+          break;
+        }
+        case JXLR_STAGE_GABORISH: {
+          GabArgs a;
+          if (!(st = make_gab_args(ctx, &p[i], fb.post, fb.gab, stride, &a, &row, &units)))
+            put_entry(hdr, at, a, row);
+          break;
+        }
+        case JXLR_STAGE_DOTS: {
+          DotArgs a;
+          if (!(st = make_dot_args(ctx, &p[i], &iop, fb.fin, stride, &a, &units)))
+            put_entry(hdr, at, a, 0);
+          break;
+        }
+        case JXLR_STAGE_SPLINES: {
+          SplineArgs a;
+          if (!(st = make_spline_args(ctx, &p[i], &iop, fb.fin, stride, fb.spline,
+                                      spline_bytes(&p[i]), &a, &units)))
+            put_entry(hdr, at, a, 0);
+          break;
+        }
+      }
+      const long long nu = (long long)ostart[k].back() + units;
+      if (!st && nu > INT32_MAX / 2) st = JXLR_E_SIZE;
+      if (!st) ostart[k].push_back(int(nu));
+    }
     if (st) return st;
     d.epf_iters = p[i].epf_iters;
     d.tiles_x = tiles_x(&p[i]);
@@ -4055,23 +4421,20 @@ jxlr_status jxlr_batch_prepare(jxlr_ctx* ctx, int n, const jxlr_frame_params* p,
     tframe.resize(tstart[i + 1], i);
     rstart[i + 1] = rstart[i] + regions_of(&p[i]);
     max_epf = std::max(max_epf, p[i].epf_iters);
+    any_noise |= p[i].noise;
   }
+  std::memcpy(hdr.data() + L.frames, frames.data(), sizeof(FrameDesc) * n);
+  std::memcpy(hdr.data() + L.tile_frame, tframe.data(), sizeof(int) * tframe.size());
+  std::memcpy(hdr.data() + L.tile_start, tstart.data(), sizeof(int) * (n + 1));
+  std::memcpy(hdr.data() + L.region_start, rstart.data(), sizeof(int) * (n + 1));
+  for (int k = 0; k < kOptStages; ++k)
+    std::memcpy(hdr.data() + L.opt_start[k], ostart[k].data(), sizeof(int) * ostart[k].size());
   DeviceGuard g(ctx->device);
   if (!g.ok) return JXLR_E_HIP;
-  // the descriptors are copied in order on the caller's stream (after any
-  // earlier batch on it that may still read this workspace) and the call
-  // returns once they are in place, so the host arrays may go away
-  hipError_t e = hipMemcpyAsync(base + L.frames, frames.data(), sizeof(FrameDesc) * n,
-                                hipMemcpyHostToDevice, stream);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(base + L.tile_frame, tframe.data(), sizeof(int) * tframe.size(),
-                       hipMemcpyHostToDevice, stream);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(base + L.tile_start, tstart.data(), sizeof(int) * (n + 1),
-                       hipMemcpyHostToDevice, stream);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(base + L.region_start, rstart.data(), sizeof(int) * (n + 1),
-                       hipMemcpyHostToDevice, stream);
+  // the header is copied in order on the caller's stream (after any earlier
+  // batch on it that may still read this workspace) and the call returns
+  // once it is in place, so the host arrays may go away
+  hipError_t e = hipMemcpyAsync(base, hdr.data(), hdr.size(), hipMemcpyHostToDevice, stream);
   if (e == hipSuccess) e = hipStreamSynchronize(stream);
   if (e != hipSuccess) return JXLR_E_HIP;
   plan->ws = ws;
@@ -4082,10 +4445,17 @@ jxlr_status jxlr_batch_prepare(jxlr_ctx* ctx, int n, const jxlr_frame_params* p,
   plan->max_epf_iters = max_epf;
   plan->any_split = 0;
   for (int i = 0; i < n; ++i) plan->any_split |= p[i].idct_split;
+  plan->any_noise = any_noise;
   plan->frames_offset = L.frames;
   plan->tile_frame_offset = L.tile_frame;
   plan->tile_start_offset = L.tile_start;
   plan->region_start_offset = L.region_start;
+  for (int k = 0; k < kOptStages; ++k) {
+    plan->opt_frames[k] = L.opt_frames[k];
+    plan->opt_units[k] = ostart[k].back();
+    plan->opt_entries_offset[k] = L.opt_entries[k];
+    plan->opt_start_offset[k] = L.opt_start[k];
+  }
   return JXLR_OK;
 }
 
@@ -4097,11 +4467,14 @@ jxlr_status jxlr_batch_run(jxlr_ctx* ctx, const jxlr_batch_plan* plan,
   if (!g.ok) return JXLR_E_HIP;
   const jxlr_launch_config c = cfg ? *cfg : jxlr_launch_config{};
   if ((st = launch_stage(ctx, plan, JXLR_STAGE_INFO, c.grid_info, 0, 0, stream))) return st;
+  if ((st = launch_stage(ctx, plan, JXLR_STAGE_PRED, 0, 0, 0, stream))) return st;
   if ((st = launch_stage(ctx, plan, JXLR_STAGE_RECON, c.grid_recon, c.order_recon, 0, stream)))
     return st;
   for (int k = 0; k < plan->max_epf_iters; ++k)
     if ((st = launch_stage(ctx, plan, JXLR_STAGE_EPF, c.grid_epf, c.order_epf, k, stream)))
       return st;
+  for (int s = JXLR_STAGE_QCO; s <= JXLR_STAGE_SPLINES; ++s)
+    if ((st = launch_stage(ctx, plan, s, 0, 0, 0, stream))) return st;
   return launch_stage(ctx, plan, JXLR_STAGE_FINISH, c.grid_finish, c.order_finish, 0, stream);
 }
 
@@ -4109,7 +4482,7 @@ jxlr_status jxlr_batch_stage(jxlr_ctx* ctx, const jxlr_batch_plan* plan, int sta
                              int order, int epf_pass, hipStream_t stream) {
   jxlr_status st = check_plan(ctx, plan);
   if (st) return st;
-  if (stage < 0 || stage > JXLR_STAGE_FINISH || order < 0 || order > 1 || epf_pass < 0 ||
+  if (stage < 0 || stage > JXLR_STAGE_SPLINES || order < 0 || order > 1 || epf_pass < 0 ||
       (stage == JXLR_STAGE_EPF && epf_pass >= plan->max_epf_iters))
     return JXLR_E_PARAM;
   DeviceGuard g(ctx->device);
@@ -4143,7 +4516,9 @@ jxlr_status jxlr_autotune(jxlr_ctx* ctx, const jxlr_batch_plan* plan, int reps,
                               ? reinterpret_cast<const void*>(recon_batch_kernel<true, true>)
                               : reinterpret_cast<const void*>(recon_batch_kernel<true, false>),
                           reinterpret_cast<const void*>(epf_batch_kernel<true>),
-                          reinterpret_cast<const void*>(finish_batch_kernel<true>)};
+                          plan->any_noise
+                              ? reinterpret_cast<const void*>(finish_batch_kernel<true, true>)
+                              : reinterpret_cast<const void*>(finish_batch_kernel<true, false>)};
   const int threads[3] = {kRecThreads, kEpfThreads, fin_threads<kFinRowsBatch>()};
   jxlr_launch_config out{};
   float total_ms = 0.0f;

@@ -112,7 +112,9 @@ class BatchPlan(C.Structure):
         ("frames_offset", C.c_size_t), ("tile_frame_offset", C.c_size_t),
         ("tile_start_offset", C.c_size_t),
         ("region_start_offset", C.c_size_t),
-        ("any_split", C.c_int),
+        ("any_split", C.c_int), ("any_noise", C.c_int),
+        ("opt_frames", C.c_int * 7), ("opt_units", C.c_int * 7),
+        ("opt_entries_offset", C.c_size_t * 7), ("opt_start_offset", C.c_size_t * 7),
     ]
 
 
@@ -126,6 +128,8 @@ class LaunchConfig(C.Structure):
 
 
 STAGE_INFO, STAGE_RECON, STAGE_EPF, STAGE_FINISH = 0, 1, 2, 3
+(STAGE_PRED, STAGE_QCO, STAGE_PATCHES, STAGE_NOISE, STAGE_GABORISH, STAGE_DOTS,
+ STAGE_SPLINES) = range(4, 11)
 
 
 class Jpeg1Params(C.Structure):

@@ -37,19 +37,32 @@ def _rounded(n):
     return -(-n // _ALLOC) * _ALLOC
 
 
-def footprint_bytes(p):
+# the optional inputs a request may carry (patches, dots, DcQuantField,
+# splines), each uploaded as one tensor of its own
+_OPTIONAL = ("patch_place", "patch_samples", "dots", "dc_quant", "spline_offsets",
+             "spline_points", "spline_dct")
+
+
+def footprint_bytes(p, frame=None):
     """Device bytes one request holds while admitted, each buffer rounded as
     the allocator rounds it: the AC (int32) and DC planes, the three maps,
-    the chroma-from-luma tiles, the output planes, and its part of the batch
-    workspace (the library's per-frame workspace plus its share of the
-    descriptor header: a frame descriptor, one int per 64x32 tile and its
-    prefix entries, which is what a batch of this frame alone adds over
+    the chroma-from-luma tiles, the optional inputs of `frame` (if given),
+    the output planes, and its part of the batch workspace (the library's
+    per-frame workspace plus its share of the descriptor header: a frame
+    descriptor, one int per 64x32 tile, its prefix entries and its option
+    stage entries, which is what a batch of this frame alone adds over
     jxlr_workspace_bytes)."""
     W, H = p.xsize, p.ysize
     Wb, Hb = (W + 7) // 8, (H + 7) // 8
     Wt, Ht = (W + 63) // 64, (H + 63) // 64
     inputs = (_rounded(3 * 64 * Wb * Hb * 4) + _rounded(3 * Wb * Hb * 4) + 3 * _rounded(Wb * Hb) +
               2 * _rounded(Wt * Ht * 4))
+    if frame is not None:
+        for k in _OPTIONAL:
+            a = frame.get(k)
+            if a is not None and len(a):
+                nb = a.numel() * a.element_size() if hasattr(a, "numel") else np.asarray(a).size * 4
+                inputs += _rounded(nb)
     out = _rounded(3 * W * H * _OUT_BYTES[p.out_format])
     return inputs + out + J.batch_workspace_bytes([p])
 
@@ -63,7 +76,7 @@ class Request:
         self.t_arrival = t_arrival
         self.frame = frame
         self.params = params
-        self.fp = footprint_bytes(params)
+        self.fp = footprint_bytes(params, frame)
         self.df = self.out = self.host_out = self.ev_up = self.ev_done = None
         self.t_done = None
         self.keep = keep

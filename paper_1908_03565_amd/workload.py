@@ -422,6 +422,62 @@ def with_splines(f, n, seed, **kw):
     return f
 
 
+def with_patches(f, n, seed):
+    """The frame dict f with n already-decoded patch placements (K.3): six
+    patch types of random sizes 1..16 with small integer residual samples
+    in [-4, 4] (larger ones push XYB far out of range and linear RGB, a
+    cube, to thousands), placed inside the frame, every fifth one against
+    the right edge and every seventh against the bottom edge."""
+    rng = np.random.default_rng(seed)
+    W, H = f["xsize"], f["ysize"]
+    sizes = [(int(rng.integers(1, 17)), int(rng.integers(1, 17))) for _ in range(6)]
+    samples, offs = [], []
+    off = 0
+    for xs, ys in sizes:
+        xs, ys = min(xs, W), min(ys, H)
+        offs.append(off)
+        samples.append(rng.integers(-4, 5, size=3 * xs * ys))
+        off += 3 * xs * ys
+    sizes = [(min(xs, W), min(ys, H)) for xs, ys in sizes]
+    place = []
+    for k in range(n):
+        t = int(rng.integers(0, 6))
+        xs, ys = sizes[t]
+        x = int(rng.integers(0, W - xs + 1)) if k % 5 else W - xs
+        y = int(rng.integers(0, H - ys + 1)) if k % 7 else H - ys
+        place.append([x, y, xs, ys, offs[t]])
+    f = dict(f)
+    f["patch_place"] = np.array(place, np.int32)
+    f["patch_samples"] = np.concatenate(samples).astype(np.int32)
+    return f
+
+
+def with_dots(f, n, seed):
+    """The frame dict f with n already-decoded dots (C.4.5's ten integers
+    each): centres in fifths of a pixel over the frame and a pixel past it,
+    every size, angle, sign and colour code, about half of them circular
+    (then the two sizes agree)."""
+    rng = np.random.default_rng(seed)
+    W, H = f["xsize"], f["ysize"]
+    d = np.zeros((n, 10), np.int64)
+    d[:, 0] = rng.integers(-5, 5 * W + 5, size=n)
+    d[:, 1] = rng.integers(-5, 5 * H + 5, size=n)
+    d[:, 2] = rng.integers(0, 16, size=n)
+    d[:, 3] = rng.integers(0, 16, size=n)
+    d[:, 4] = rng.integers(0, 8, size=n)
+    d[:, 5] = rng.integers(0, 8, size=n)
+    d[:, 6] = rng.integers(0, 10, size=n)
+    d[:, 7] = rng.integers(0, 36, size=n)
+    d[:, 8] = rng.integers(0, 10, size=n)
+    d[:, 9] = rng.integers(0, 2, size=n)
+    d[d[:, 9] == 1, 3] = d[d[:, 9] == 1, 2]
+    d[:, 0] = np.clip(d[:, 0], 0, None)  # positions are unsigned
+    d[:, 1] = np.clip(d[:, 1], 0, None)
+    f = dict(f)
+    f["dots"] = d.astype(np.int32)
+    return f
+
+
 def jpeg1(W, H, seed, hs=(2, 1, 1), vs=(2, 1, 1), grey=False):
     """A synthetic recompressed JPEG1 frame (M.4 already decoded) of W x H
     pixels: per component the quantized coefficients int32 [8 hib][8 wib]

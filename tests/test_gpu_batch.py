@@ -248,3 +248,133 @@ def test_batch_xcd_order(ctx, order):
         torch.cuda.synchronize()
         for i, (o, r) in enumerate(zip(outs, ref)):
             np.testing.assert_array_equal(o.cpu().numpy(), r, err_msg=f"grid {grid} frame {i}")
+
+
+# Frames with the path's options, alone and together, beside plain ones:
+# (w, h, epf_iters, out_format, gab, options).  "field" adds a DcQuantField
+# with extra levels (1, 2, 3) under smoothing and AC prediction.
+OPT_MIX = [
+    (96, 72, 2, 0, 1, {}),
+    (130, 97, 1, 1, 1, dict(ac_prediction=1, dc_smoothing=1)),
+    (200, 136, 2, 0, 1, dict(qco=1)),
+    (96, 72, 3, 2, 1, dict(qco=1)),
+    (131, 77, 1, 0, 1, dict(patches=25)),
+    (257, 66, 0, 1, 1, dict(noise=1)),
+    (192, 136, 1, 0, 1, dict(dots=300, noise=1)),
+    (160, 96, 2, 0, 0, dict(splines=6)),
+    (136, 80, 2, 0, 1, dict(field=1, ac_prediction=1, dc_smoothing=1, qco=1)),
+    (300, 264, 2, 0, 1, dict(ac_prediction=1, qco=1, patches=40, noise=1, dots=200, splines=5)),
+    (64, 32, 0, 0, 0, dict(qco=1, patches=3)),
+]
+# frames whose option stages add with float atomics (order-dependent sums)
+ATOMIC = ("patches", "dots", "splines")
+
+
+def _opt_frames(mix, seed0):
+    from paper_1908_03565_amd import jxlr as J
+    frames, ps = [], []
+    for i, (w, h, e, fmt, g, o) in enumerate(mix):
+        seed = seed0 + i
+        f = wl.frame(w, h, seed=seed, epf_iters=e, out_format=fmt, gab=g)
+        kw = dict(f["params"])
+        if o.get("field"):
+            kw["extra_levels"] = (1, 2, 3)
+            f["dc_quant"] = wl.dc_quant_field(np.random.default_rng(seed), f, (1, 2, 3))
+        for k in ("ac_prediction", "dc_smoothing", "qco", "noise"):
+            if o.get(k):
+                kw[k] = 1
+        if o.get("noise"):
+            kw["noise_lut"] = np.linspace(0.01, 0.08, 16)
+        if o.get("patches"):
+            f = wl.with_patches(f, o["patches"], seed)
+            kw["num_patches"] = o["patches"]
+        if o.get("dots"):
+            f = wl.with_dots(f, o["dots"], seed)
+            kw["num_dots"] = o["dots"]
+            kw["dot_colour_quant"] = (0.004, 0.02, 0.01)
+        if o.get("splines"):
+            f = wl.with_splines(f, o["splines"], seed)
+            kw["num_splines"] = o["splines"]
+            kw["num_spline_points"] = len(f["spline_points"])
+        p = J.params(w, h, out_format=fmt, **kw)
+        assert J.validate_maps_host(p, f) == 0
+        frames.append(f)
+        ps.append(p)
+    return frames, ps
+
+
+def _agree(got, ref, atomic, msg):
+    """Bit-identical, except where float atomics sum in another order: then
+    within binary32 rounding of the sums (f32), or one code on a few samples."""
+    if not atomic:
+        np.testing.assert_array_equal(got, ref, err_msg=msg)
+    elif got.dtype == np.float32:
+        scale = max(1.0, float(np.abs(ref).max()))
+        assert np.abs(got.astype(np.float64) - ref).max() <= 1e-5 * scale, msg
+    else:
+        d = np.abs(got.astype(np.int64) - ref.astype(np.int64))
+        assert d.max() <= 1 and (d > 0).mean() <= 1e-3, msg
+
+
+def test_batch_with_options_equals_single_frame_decode(ctx):
+    import torch
+    from paper_1908_03565_amd import jxlr as J
+    frames, ps = _opt_frames(OPT_MIX, 1700)
+    dfs = [J.DeviceFrame(f) for f in frames]
+    ref = _singles(ctx, ps, dfs)
+    outs = [ctx.empty_out(p) for p in ps]
+    ios = [df.io(o) for df, o in zip(dfs, outs)]
+    ws = ctx.batch_workspace(ps)
+    plan = ctx.batch_prepare(ps, ios, ws)
+    # every option stage has its frames
+    names = ["ac_prediction", "qco", "num_patches", "noise", None, "num_dots", "num_splines"]
+    for k, nm in enumerate(names):
+        if nm is None:  # Gaborish as its own pass: gab with dots or splines
+            want = sum(1 for p in ps if p.gab and (p.num_dots or p.num_splines))
+        elif nm == "qco":
+            want = sum(1 for p in ps if p.qco and p.epf_iters > 0)
+        else:
+            want = sum(1 for p in ps if getattr(p, nm))
+        assert plan.opt_frames[k] == want, (k, nm)
+    assert plan.any_noise == 1
+    _fill(outs)
+    ctx.batch_run(plan)
+    torch.cuda.synchronize()
+    assert ctx.device_status() == 0
+    for i, (o, r) in enumerate(zip(outs, ref)):
+        atomic = any(OPT_MIX[i][5].get(k) for k in ATOMIC)
+        _agree(o.cpu().numpy(), r, atomic, f"frame {i} {OPT_MIX[i]}")
+    # persistent grids for the tile stages change nothing
+    _fill(outs)
+    ctx.batch_run(plan, J.LaunchConfig(3, 5, 7, 2, 1, 0, 1))
+    torch.cuda.synchronize()
+    for i, (o, r) in enumerate(zip(outs, ref)):
+        atomic = any(OPT_MIX[i][5].get(k) for k in ATOMIC)
+        _agree(o.cpu().numpy(), r, atomic, f"grid run, frame {i}")
+
+
+def test_batch_with_options_graph_replays(ctx):
+    import torch
+    from paper_1908_03565_amd import jxlr as J
+    frames, ps = _opt_frames(OPT_MIX[1:7], 1900)
+    dfs = [J.DeviceFrame(f) for f in frames]
+    outs = [ctx.empty_out(p) for p in ps]
+    ios = [df.io(o) for df, o in zip(dfs, outs)]
+    ws = ctx.batch_workspace(ps)
+    plan = ctx.batch_prepare(ps, ios, ws)
+    ctx.batch_run(plan)
+    torch.cuda.synchronize()
+    eager = [o.cpu().numpy() for o in outs]
+    g = ctx.graph(plan)
+    for rep in range(3):
+        _fill(outs)
+        torch.cuda.synchronize()
+        g.launch()
+        torch.cuda.synchronize()
+        for i, (o, e) in enumerate(zip(outs, eager)):
+            atomic = any(OPT_MIX[1 + i][5].get(k) for k in ATOMIC)
+            _agree(o.cpu().numpy(), e, atomic, f"replay {rep} frame {i}")
+        ctx.decode(ps[0], dfs[0], ctx.empty_out(ps[0]), ctx.workspace(ps[0]))
+        torch.cuda.synchronize()
+    g.close()
+    assert ctx.device_status() == 0

@@ -18,28 +18,6 @@ def ctx():
     return J.Context(0)
 
 
-def _with_dots(f, n, seed):
-    rng = np.random.default_rng(seed)
-    W, H = f["xsize"], f["ysize"]
-    d = np.zeros((n, 10), np.int64)
-    d[:, 0] = rng.integers(-5, 5 * W + 5, size=n)
-    d[:, 1] = rng.integers(-5, 5 * H + 5, size=n)
-    d[:, 2] = rng.integers(0, 16, size=n)
-    d[:, 3] = rng.integers(0, 16, size=n)
-    d[:, 4] = rng.integers(0, 8, size=n)
-    d[:, 5] = rng.integers(0, 8, size=n)
-    d[:, 6] = rng.integers(0, 10, size=n)
-    d[:, 7] = rng.integers(0, 36, size=n)
-    d[:, 8] = rng.integers(0, 10, size=n)
-    d[:, 9] = rng.integers(0, 2, size=n)
-    d[d[:, 9] == 1, 3] = d[d[:, 9] == 1, 2]
-    d[:, 0] = np.clip(d[:, 0], 0, None)  # positions are unsigned
-    d[:, 1] = np.clip(d[:, 1], 0, None)
-    f = dict(f)
-    f["dots"] = d.astype(np.int32)
-    return f
-
-
 @pytest.mark.parametrize("W,H,seed,n,gab,noise", [(192, 136, 141, 300, 1, 0), (131, 77, 142, 120, 0, 0),
                                                   (300, 264, 143, 500, 1, 1),
                                                   # centres far from the origin, where a
@@ -47,7 +25,7 @@ def _with_dots(f, n, seed):
                                                   (2056, 96, 144, 2000, 1, 0)])
 def test_dots_end_to_end(ctx, W, H, seed, n, gab, noise):
     from paper_1908_03565_amd import jxlr as J
-    f = _with_dots(wl.small(W, H, seed=seed, epf_iters=1), n, seed)
+    f = wl.with_dots(wl.small(W, H, seed=seed, epf_iters=1), n, seed)
     kw = dict(f["params"], gab=gab, noise=noise, noise_lut=np.full(16, 0.05),
               dot_colour_quant=(0.004, 0.02, 0.01))
     p = J.params(W, H, num_dots=n, **kw)

@@ -18,37 +18,11 @@ def ctx():
     return J.Context(0)
 
 
-def _with_patches(f, n, seed):
-    """n placements of 6 random patch types (sizes 1..16) inside the frame."""
-    rng = np.random.default_rng(seed)
-    W, H = f["xsize"], f["ysize"]
-    sizes = [(int(rng.integers(1, 17)), int(rng.integers(1, 17))) for _ in range(6)]
-    samples, offs = [], []
-    off = 0
-    for xs, ys in sizes:
-        offs.append(off)
-        # small residual-like samples: larger ones push XYB far out of range
-        # and linear RGB (a cube) to thousands
-        samples.append(rng.integers(-4, 5, size=3 * xs * ys))
-        off += 3 * xs * ys
-    place = []
-    for k in range(n):
-        t = int(rng.integers(0, 6))
-        xs, ys = sizes[t]
-        x = int(rng.integers(0, W - xs + 1)) if k % 5 else W - xs  # some at the edge
-        y = int(rng.integers(0, H - ys + 1)) if k % 7 else H - ys
-        place.append([x, y, xs, ys, offs[t]])
-    f = dict(f)
-    f["patch_place"] = np.array(place, np.int32)
-    f["patch_samples"] = np.concatenate(samples).astype(np.int32)
-    return f
-
-
 @pytest.mark.parametrize("W,H,seed,n,iters", [(192, 136, 121, 40, 2), (131, 77, 122, 25, 1),
                                               (300, 264, 123, 200, 0)])
 def test_patches_end_to_end(ctx, W, H, seed, n, iters):
     from paper_1908_03565_amd import jxlr as J
-    f = _with_patches(wl.small(W, H, seed=seed, epf_iters=iters), n, seed)
+    f = wl.with_patches(wl.small(W, H, seed=seed, epf_iters=iters), n, seed)
     p = J.params(W, H, num_patches=n, **f["params"])
     df = J.DeviceFrame(f)
     gpu = P.gpu_stages(ctx, p, df)
@@ -74,7 +48,7 @@ def test_patches_end_to_end(ctx, W, H, seed, n, iters):
 
 def test_ill_formed_patch_sets_the_flag(ctx):
     from paper_1908_03565_amd import jxlr as J
-    f = _with_patches(wl.small(64, 48, seed=124, epf_iters=0), 3, 124)
+    f = wl.with_patches(wl.small(64, 48, seed=124, epf_iters=0), 3, 124)
     f["patch_place"][1] = [60, 0, 8, 8, 0]  # leaves the frame
     p = J.params(64, 48, num_patches=3, **f["params"])
     df = J.DeviceFrame(f)

@@ -176,13 +176,16 @@ def test_batch_workspace_bytes():
     assert J.batch_workspace_bytes(ps[:1]) > J.workspace_bytes(ps[0])
     assert J.batch_workspace_bytes([]) == 0
     assert J.batch_workspace_bytes(ps + [J.params(64, 64, epf_iters=4)]) == 0
-    # the batch stages have no constraint pass
-    assert J.batch_workspace_bytes(ps + [J.params(64, 64, qco=1)]) == 0
-    assert J.batch_workspace_bytes(ps + [J.params(64, 64, ac_prediction=1)]) == 0
-    assert J.batch_workspace_bytes(ps + [J.params(64, 64, noise=1)]) == 0
-    assert J.batch_workspace_bytes(ps + [J.params(64, 64, num_patches=3)]) == 0
-    assert J.batch_workspace_bytes(ps + [J.params(64, 64, num_dots=3)]) == 0
-    assert J.batch_workspace_bytes(ps + [J.params(64, 64, num_splines=1, num_spline_points=2)]) == 0
+    # frames with options carry their single-frame workspace (prediction sums,
+    # the constraint's third buffer, noise channels, the Gaborish plane,
+    # spline samples) plus one table entry per option stage they take
+    opts = [dict(qco=1, epf_iters=2), dict(ac_prediction=1), dict(noise=1), dict(num_patches=3),
+            dict(num_dots=3, gab=1), dict(num_splines=1, num_spline_points=2)]
+    for o in opts:
+        q = J.params(64, 64, **o)
+        extra = J.batch_workspace_bytes(ps + [q]) - total
+        assert extra >= J.workspace_bytes(q), o
+        assert extra <= J.workspace_bytes(q) + 256 * 8 + 4096, o
 
 
 # --- the library's constant tables versus the oracle's --------------------
