@@ -35,12 +35,13 @@ sys.path.insert(0, ROOT)
 
 # Peaks of one MI355X used for the roofline fractions.
 HBM_PEAK_GBS = 8000.0
-# Plain 32-bit VALU issue: the fp32 vector peak of 157.3 TFLOP/s with an FMA
-# counted as one op, i.e. 256 CUs x 4 SIMD x 32 lanes x 2.4 GHz (two wave64
-# instructions per CU per clock).  Simple ops (adds, logic, FMA) issue at
-# this rate; the packed-byte SAD, three-input adds and 24-bit multiplies at
-# half of it.
-ALU_PEAK_TOPS = 256 * 4 * 32 * 2.4e9 / 1e12
+# 32-bit VALU lane operations without packed math: 256 CUs x 4 SIMDs x 16
+# lanes x 2.4 GHz = 39.3 T ops/s (a wave64 instruction occupies its 16-lane
+# SIMD for four clocks).  The fp32 vector figure of 157.3 TFLOP/s is this
+# rate x 2 (an FMA counted as two flops) x 2 (packed FP32, two floats per
+# lane), which the integer SAD, compare and select ops cannot use and which
+# the build disables.
+ALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 # Algorithmic work per pixel of one EPF pass (separable formulation): for each
 # of the 56 window offsets, one packed 3-channel SAD of the new sample pair,
 # 3 + 2 adds of the 4x3 patch box sum, 6 ops of Weight and the threshold,

@@ -1575,17 +1575,19 @@ __device__ __attribute__((always_inline)) inline void qco_tile(const QcoArgs& a,
 // Edge-preserving filter (J.2), one pass.
 //
 // One workgroup per 64x32 output tile (two 32x32 regions side by side); each
-// thread filters an 8-pixel vertical strip of one column.  The tile and its
-// filter halo are staged in LDS once:
-//   s_in  input samples of columns x0-3..x0+68 and rows y0-3..y0+34 (the
-//         7x8 window of every output pixel);
-//   s_p   per channel, 32-bit words packing the guide bytes of 4 consecutive
-//         columns, for start columns x0-4..x0+66 and rows y0-4..y0+35.
-// A J.2.3 patch is 4 columns by 3 rows, so one v_sad_u8 on two such words is
+// thread filters a vertical strip of kEpfRows pixels of one column.  The
+// tile and its filter halo (rows y0-4..y0+35, start columns x0-4..x0+67) are
+// staged in LDS once, as one 16-byte cell per row and start column s:
+//   s_q[v][s] = the guide words of channels 0, 1, 2 packing the guide bytes
+//               of columns s..s+3, and the channel-0 input sample of column
+//               s+1;
+//   s_r[v][s] = the channel-1 and channel-2 input samples of column s+1.
+// A J.2.3 patch is 4 columns by 3 rows, so one v_sad_u8 on two guide words is
 // one channel's distance over one patch row.  For a window offset (cx, cy)
 // the distance of the strip's pixel in row y is rs(y-1) + rs(y) + rs(y+1),
-// rs(y') = sum_c sad(P_c(x-1, y'), P_c(x-1+cx, y'+cy)); the strip's ten row
-// sums serve its eight overlapping patches.
+// rs(y') = sum_c sad(P_c(x-1, y'), P_c(x-1+cx, y'+cy)); the strip's row sums
+// serve its overlapping patches.  A window column is one 16-byte and one
+// 8-byte LDS read per row, all at immediate offsets from two addresses.
 
 // a + b + c in one v_add3_u32.  Written out because the compiler otherwise
 // shares pair sums between neighbouring box sums, which costs more adds.
@@ -1640,9 +1642,8 @@ constexpr int kEpfTW = 64, kEpfTH = 32;  // output tile
 constexpr int kEpfRows = 4;
 constexpr int kEpfThreads = kEpfTW * kEpfTH / kEpfRows;
 constexpr int kEpfMinBlocks = 2;
-constexpr int kInW = 72, kInH = 38;      // s_in: columns x0-4.., rows y0-3..
-constexpr int kPW = 72, kPH = 40;        // s_p: start columns x0-4.., rows y0-4..
-constexpr int kGW = 19;                  // packed guide words per row: columns x0-4..x0+71
+constexpr int kQW = 72, kQH = 40;  // cells per row (start columns x0-4..), rows y0-4..
+constexpr int kGW = 19;            // packed guide words per row: columns x0-4..x0+71
 
 __device__ inline uint32_t guide_byte(float v, float minv, float scale) {
   // J.2.2 in binary32: floor(clamp((v - min) * scale, 0, 255))
@@ -1654,11 +1655,9 @@ __device__ inline uint32_t guide_byte(float v, float minv, float scale) {
 // One 64x32 output tile of an EPF pass.  Threads may return after the last
 // barrier.
 __device__ __attribute__((always_inline)) inline void epf_tile(const EpfArgs& a, int tbx, int tby) {
-  // 16-byte aligned rows (72 words): stage A and B store four words at once
-  __shared__ __attribute__((aligned(16))) float s_in[3][kInH][kInW];
-  __shared__ __attribute__((aligned(16))) uint32_t s_p[3][kPH][kPW];
-  static_assert(kInW % 4 == 0 && kPW % 4 == 0, "16-byte rows");
-  __shared__ uint32_t s_w[3][kPH][kGW + 1];
+  __shared__ uint4 s_q[kQH][kQW];
+  __shared__ float2 s_r[kQH][kQW];
+  __shared__ uint32_t s_w[3][kQH][kGW + 1];
   __shared__ float s_rng[32];
   __shared__ int s_mul[32];
   __shared__ uint32_t s_sadmax[32];
@@ -1671,12 +1670,13 @@ __device__ __attribute__((always_inline)) inline void epf_tile(const EpfArgs& a,
   const int gbx0 = x0 / 8, gby0 = y0 / 8;
   const size_t plane = size_t(a.H) * a.stride;
 
-  // A: input samples and packed guide words (4 columns per word).  Tiles
-  // whose halo lies inside the frame skip the mirroring and, with a row
-  // stride that keeps 16-byte alignment, load four columns at once.
-  const bool interior = x0 >= 4 && x0 + 4 * kGW - 4 <= a.W && y0 >= 4 && y0 + kPH - 4 <= a.H;
+  // A: input samples and packed guide words (4 columns per word) of rows
+  // y0-4.. and columns x0-4..x0+71.  Tiles whose halo lies inside the frame
+  // skip the mirroring and, with a row stride that keeps 16-byte alignment,
+  // load four columns at once.  Sample column x0-4+k goes to cell k-1.
+  const bool interior = x0 >= 4 && x0 + 4 * kGW - 4 <= a.W && y0 >= 4 && y0 + kQH - 4 <= a.H;
   const bool vec = interior && (a.stride & 3) == 0 && (reinterpret_cast<uintptr_t>(a.in) & 15) == 0;
-  for (int it = tid; it < kPH * kGW; it += kEpfThreads) {
+  for (int it = tid; it < kQH * kGW; it += kEpfThreads) {
     const int v = it / kGW, g = it % kGW;
     const int gy = interior ? y0 - 4 + v : mirror(y0 - 4 + v, a.H);
     float vals[3][4];
@@ -1707,35 +1707,37 @@ __device__ __attribute__((always_inline)) inline void epf_tile(const EpfArgs& a,
       for (int j = 0; j < 4; ++j) w |= guide_byte(vals[c][j], a.minv[c], a.scale[c]) << (8 * j);
       s_w[c][v][g] = w;
     }
-    // the four samples as one 16-byte store per channel (s_in columns start
-    // at x0 - 4 like the words)
-    const int ri = v - 1;
-    if (ri >= 0 && ri < kInH && 4 * g < kInW) {
 #pragma unroll
-      for (int c = 0; c < 3; ++c)
-        *reinterpret_cast<float4*>(&s_in[c][ri][4 * g]) =
-            make_float4(vals[c][0], vals[c][1], vals[c][2], vals[c][3]);
+    for (int j = 0; j < 4; ++j) {
+      const int k = 4 * g + j - 1;
+      if (k >= 0 && k < kQW) {
+        s_q[v][k].w = __float_as_uint(vals[0][j]);
+        s_r[v][k] = make_float2(vals[1][j], vals[2][j]);
+      }
     }
   }
   if (tid < 2) s_bad[tid] = 0;
   if (tid == 2) s_clamp = 0;
   __syncthreads();
 
-  // B: guide words at every start column (four per aligned word pair).
-  for (int it = tid; it < 3 * kPH * (kGW - 1); it += kEpfThreads) {
-    const int c = it / (kPH * (kGW - 1));
-    const int rem = it - c * (kPH * (kGW - 1));
-    const int v = rem / (kGW - 1), g = rem - v * (kGW - 1);
-    const uint32_t lo = s_w[c][v][g], hi = s_w[c][v][g + 1];
-    // one 16-byte store (the last word of the row is never read)
-    *reinterpret_cast<uint4*>(&s_p[c][v][4 * g]) =
-        make_uint4(lo, __builtin_amdgcn_alignbyte(hi, lo, 1), __builtin_amdgcn_alignbyte(hi, lo, 2),
-                   __builtin_amdgcn_alignbyte(hi, lo, 3));
+  // B: guide words at every start column (from each aligned word pair).
+  for (int it = tid; it < kQH * (kGW - 1) * 4; it += kEpfThreads) {
+    const int k = it & 3, vg = it >> 2;
+    const int v = vg / (kGW - 1), g = vg - v * (kGW - 1);
+    uint32_t wd[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      wd[c] = __builtin_amdgcn_alignbyte(s_w[c][v][g + 1], s_w[c][v][g], k);
+    uint4& q = s_q[v][4 * g + k];
+    q.x = wd[0];
+    q.y = wd[1];
+    q.z = wd[2];
   }
   if (tid < 32) load_tile_info(a.info, a.Wb, a.Hb, gbx0, gby0, tid, s_strat, s_owner, s_bad);
+  __syncthreads();
   // Per-block range of `scaled` (J.2.4) over the block's pixels inside the
-  // frame: eight lanes per block, one column each (a wave reads whole tile
-  // rows, free of bank conflicts), reduced across the lanes.
+  // frame: eight lanes per block, one column each, reduced across the lanes.
+  // Pixel (x0 + px, y0 + py) is in cell (py + 4, px + 3).
   static_assert(kEpfThreads >= 256, "range step needs 256 threads");
   if (tid < 256) {
     const int b = tid >> 3, j = tid & 7;
@@ -1744,9 +1746,11 @@ __device__ __attribute__((always_inline)) inline void epf_tile(const EpfArgs& a,
     if (x0 + 8 * bxl + j < a.W)
       for (int r = 0; r < 8; ++r) {
         if (y0 + 8 * byl + r >= a.H) break;
+        const int v = 8 * byl + r + 4, k = 8 * bxl + j + 3;
+        const float in[3] = {__uint_as_float(s_q[v][k].w), s_r[v][k].x, s_r[v][k].y};
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-          const float sc = (s_in[c][3 + 8 * byl + r][4 + 8 * bxl + j] - a.minv[c]) * a.scale[c];
+          const float sc = (in[c] - a.minv[c]) * a.scale[c];
           lo[c] = fminf(lo[c], sc);
           hi[c] = fmaxf(hi[c], sc);
         }
@@ -1799,7 +1803,8 @@ __device__ __attribute__((always_inline)) inline void epf_tile(const EpfArgs& a,
   }
   __syncthreads();
 
-  // E: the strip of kEpfRows pixels of column x.
+  // E: the strip of kEpfRows pixels of column x: pixel row ys + i is cell
+  // row row0 + 4 + i, its patch's start column x - 1 is cell column lx + 3.
   constexpr int R = kEpfRows;
   const int lx = tid & 63, row0 = R * (tid >> 6);
   const int x = x0 + lx, ys = y0 + row0;
@@ -1815,17 +1820,23 @@ __device__ __attribute__((always_inline)) inline void epf_tile(const EpfArgs& a,
         a.guide_dbg[(size_t(c) * a.H + ys + i) * a.W + x] = uint8_t(s_w[c][row0 + 4 + i][wg] >> sh);
   }
   if (mul64 > 0) {  // sigma < 16: the pass leaves the pixel unchanged
-    for (int i = 0; i < nrows; ++i)
-      for (int c = 0; c < 3; ++c)
-        o0[c * plane + size_t(i) * a.stride] = s_in[c][row0 + 3 + i][lx + 4];
+    for (int i = 0; i < nrows; ++i) {
+      const int v = row0 + 4 + i;
+      o0[size_t(i) * a.stride] = __uint_as_float(s_q[v][lx + 3].w);
+      o0[plane + size_t(i) * a.stride] = s_r[v][lx + 3].x;
+      o0[2 * plane + size_t(i) * a.stride] = s_r[v][lx + 3].y;
+    }
     return;
   }
   const uint32_t thr = a.thr, smax = s_sadmax[bi];
   uint32_t ref[R + 2][3];
 #pragma unroll
-  for (int j = 0; j < R + 2; ++j)
-#pragma unroll
-    for (int c = 0; c < 3; ++c) ref[j][c] = s_p[c][row0 + 3 + j][lx + 3];
+  for (int j = 0; j < R + 2; ++j) {
+    const uint4 q = s_q[row0 + 3 + j][lx + 3];
+    ref[j][0] = q.x;
+    ref[j][1] = q.y;
+    ref[j][2] = q.z;
+  }
   float acc[R][4];
 #pragma unroll
   for (int i = 0; i < R; ++i)
@@ -1839,24 +1850,23 @@ __device__ __attribute__((always_inline)) inline void epf_tile(const EpfArgs& a,
   auto accumulate = [&](auto clamp_tag) {
     constexpr bool CLAMP = decltype(clamp_tag)::value;
     for (int cx = -3; cx <= 4; ++cx) {
-      uint32_t nb[R + 8][3];
-      float inp[R + 6][3];
+      // window column cx: guide words of cell rows row0 .. row0 + R + 7 and
+      // the input samples of rows row0 + 1 .. row0 + R + 6
+      uint4 nb[R + 8];
+      float2 in12[R + 6];
 #pragma unroll
-      for (int j = 0; j < R + 8; ++j)
+      for (int j = 0; j < R + 8; ++j) nb[j] = s_q[row0 + j][lx + 3 + cx];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) nb[j][c] = s_p[c][row0 + j][lx + 3 + cx];
-#pragma unroll
-      for (int j = 0; j < R + 6; ++j)
-#pragma unroll
-        for (int c = 0; c < 3; ++c) inp[j][c] = s_in[c][row0 + j][lx + 4 + cx];
+      for (int j = 0; j < R + 6; ++j) in12[j] = s_r[row0 + 1 + j][lx + 3 + cx];
 #pragma unroll
       for (int cy = -3; cy <= 3; ++cy) {
         uint32_t rs[R + 2];
 #pragma unroll
         for (int j = 0; j < R + 2; ++j) {
-          uint32_t s = __builtin_amdgcn_sad_u8(ref[j][0], nb[j + cy + 3][0], 0u);
-          s = __builtin_amdgcn_sad_u8(ref[j][1], nb[j + cy + 3][1], s);
-          rs[j] = __builtin_amdgcn_sad_u8(ref[j][2], nb[j + cy + 3][2], s);
+          const uint4 q = nb[j + cy + 3];
+          uint32_t t = __builtin_amdgcn_sad_u8(ref[j][0], q.x, 0u);
+          t = __builtin_amdgcn_sad_u8(ref[j][1], q.y, t);
+          rs[j] = __builtin_amdgcn_sad_u8(ref[j][2], q.z, t);
         }
 #pragma unroll
         for (int i = 0; i < R; ++i) {
@@ -1870,10 +1880,12 @@ __device__ __attribute__((always_inline)) inline void epf_tile(const EpfArgs& a,
             wb = select_hi(sad, smax, t);
           }
           const float w = __uint_as_float(wb);
+          // the sample of pixel row i + cy: cell row row0 + 4 + i + cy
+          const int r = i + cy + 3;
           acc[i][3] += w;
-          acc[i][0] = fmaf(w, inp[i + cy + 3][0], acc[i][0]);
-          acc[i][1] = fmaf(w, inp[i + cy + 3][1], acc[i][1]);
-          acc[i][2] = fmaf(w, inp[i + cy + 3][2], acc[i][2]);
+          acc[i][0] = fmaf(w, __uint_as_float(nb[r + 1].w), acc[i][0]);
+          acc[i][1] = fmaf(w, in12[r].x, acc[i][1]);
+          acc[i][2] = fmaf(w, in12[r].y, acc[i][2]);
         }
       }
     }
