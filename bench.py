@@ -54,6 +54,9 @@ FINISH_BYTES_PER_PX = {0: 12 + 12, 1: 12 + 3, 2: 12 + 6}
 # quantization constraint: f32 XYB before and after the filter in, the
 # constrained f32 XYB out
 QCO_BYTES_PER_PX = 12 + 12 + 12
+# reconstruction fused with the finish (frames without EPF): int32 AC in,
+# f32 / u8 / u16 RGB out
+FUSED_BYTES_PER_PX = {0: 12 + 12, 1: 12 + 3, 2: 12 + 6}
 
 METRIC = "decoded MP/s (coeffs->RGB) at stated max-abs err vs FP64; p50/p99 latency"
 
@@ -409,7 +412,7 @@ def bench_batch(args, J, wl, torch, np):
     ps, dfs, outs = [], [], []
     for i, fr in enumerate(frames):
         p = J.params(fr["xsize"], fr["ysize"], out_format=fr["out_format"],
-                     idct_split=int(args.split), **fr["params"])
+                     idct_split=int(args.split), fuse=-1 if args.no_fuse else 0, **fr["params"])
         if i > 0 and fr is frames[0]:
             df = dfs[0].clone()  # repeated inputs still get their own device memory
         else:
@@ -450,33 +453,52 @@ def bench_batch(args, J, wl, torch, np):
     value = mp / (ms_per_step / 1e3)
     log(f"bench: {ms_per_step:.4f} ms/step (graph), {value:.1f} MP/s")
 
-    # stage-by-stage loop with events between the stages (same schedule)
+    # stage-by-stage loop with events between the stages (same schedule);
+    # stages with no frame are left out
     n_epf = plan.max_epf_iters
+    fused_px = sum(p.xsize * p.ysize for p in ps if p.fuse >= 0 and p.epf_iters == 0)
+    tile_px = px - fused_px
+    stages = [("info", J.STAGE_INFO, cfg.grid_info, 0, 0)]
+    if fused_px:
+        stages += [("fused", J.STAGE_FUSED, 0, 0, 0), ("seam", J.STAGE_SEAM, 0, 0, 0)]
+    if tile_px:
+        stages.append(("reconstruct", J.STAGE_RECON, cfg.grid_recon, cfg.order_recon, 0))
+        stages += [(f"epf{k}", J.STAGE_EPF, cfg.grid_epf, cfg.order_epf, k) for k in range(n_epf)]
+        stages.append(("finish", J.STAGE_FINISH, cfg.grid_finish, cfg.order_finish, 0))
     reps = max(3, args.steps // 2)
-    sev = [[torch.cuda.Event(enable_timing=True) for _ in range(4 + n_epf)] for _ in range(reps)]
+    sev = [[torch.cuda.Event(enable_timing=True) for _ in range(len(stages) + 1)]
+           for _ in range(reps)]
     for e in sev:
         e[0].record(stream)
-        ctx.batch_stage(plan, J.STAGE_INFO, cfg.grid_info, 0, 0, stream)
-        e[1].record(stream)
-        ctx.batch_stage(plan, J.STAGE_RECON, cfg.grid_recon, cfg.order_recon, 0, stream)
-        e[2].record(stream)
-        for k in range(n_epf):
-            ctx.batch_stage(plan, J.STAGE_EPF, cfg.grid_epf, cfg.order_epf, k, stream)
-            e[3 + k].record(stream)
-        ctx.batch_stage(plan, J.STAGE_FINISH, cfg.grid_finish, cfg.order_finish, 0, stream)
-        e[3 + n_epf].record(stream)
+        for i, (_, st, grid, order, k) in enumerate(stages):
+            ctx.batch_stage(plan, st, grid, order, k, stream)
+            e[i + 1].record(stream)
     torch.cuda.synchronize()
-    stage = lambda i: statistics.mean(e[i].elapsed_time(e[i + 1]) for e in sev)
-    info_ms, recon_ms = stage(0), stage(1)
-    epf_ms = [stage(2 + k) for k in range(n_epf)]
-    fin_ms = stage(2 + n_epf)
+    sms = {nm: statistics.mean(e[i].elapsed_time(e[i + 1]) for e in sev)
+           for i, (nm, *_rest) in enumerate(stages)}
+    info_ms = sms["info"]
+    recon_ms, fin_ms = sms.get("reconstruct"), sms.get("finish")
+    epf_ms = [sms[f"epf{k}"] for k in range(n_epf) if f"epf{k}" in sms]
     eager_ms = statistics.mean(e[0].elapsed_time(e[-1]) for e in sev)
-    log(f"bench: eager stages: info {info_ms:.4f} recon {recon_ms:.4f} epf "
-        f"{['%.4f' % x for x in epf_ms]} finish {fin_ms:.4f} (sum {eager_ms:.4f} ms)")
+    log(f"bench: eager stages {({k: round(v, 4) for k, v in sms.items()})} (sum {eager_ms:.4f} ms)")
     fmt = ps[0].out_format
-    kernels = kernel_table(px, recon_ms, statistics.mean(epf_ms) if n_epf else None, fin_ms, fmt,
-                           ("recon_batch_kernel", "epf_batch_kernel", "finish_batch_kernel"))
+    kernels = {}
+    if tile_px:
+        kernels = kernel_table(tile_px, recon_ms, statistics.mean(epf_ms) if n_epf else None,
+                               fin_ms, fmt,
+                               ("recon_batch_kernel", "epf_batch_kernel", "finish_batch_kernel"))
+    if fused_px:
+        fb = FUSED_BYTES_PER_PX[fmt]
+        kernels["fused_batch_kernel"] = dict(
+            ms=sms["fused"], bound="hbm", bytes_per_px=fb,
+            achieved=fused_px * fb / (sms["fused"] / 1e3) / 1e9)
     roofline = roofline_of(kernels, {"epf_batch_kernel": n_epf}, name, px)
+    # the whole step against the algorithmic bytes of the path (coefficients
+    # in, output out; maps and DC add under 0.3 B/px)
+    e2e_bpp = FUSED_BYTES_PER_PX[fmt]
+    e2e = dict(bytes_per_px=e2e_bpp, achieved=round(px * e2e_bpp / (ms_per_step / 1e3) / 1e9, 1),
+               peak=HBM_PEAK_GBS, unit="GB/s",
+               frac=round(px * e2e_bpp / (ms_per_step / 1e3) / 1e9 / HBM_PEAK_GBS, 4))
 
     # every frame of the batch equals its single-frame decode; a sample of
     # frames against the oracle
@@ -553,11 +575,11 @@ def bench_batch(args, J, wl, torch, np):
                    else "f32"},
         "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 5),
                        "p99": round(float(np.percentile(lat, 99)), 5)},
-        "stage_ms": {"info": round(info_ms, 5), "reconstruct": round(recon_ms, 5),
-                     "epf": [round(x, 5) for x in epf_ms], "finish": round(fin_ms, 5),
-                     "eager_sum": round(eager_ms, 5)},
+        "stage_ms": {**{k: round(v, 5) for k, v in sms.items() if not k.startswith("epf")},
+                     "epf": [round(x, 5) for x in epf_ms], "eager_sum": round(eager_ms, 5)},
         "host_wall_ms_per_step": round(wall / args.steps * 1e3, 5),
         "error": err,
+        "end_to_end_hbm": e2e,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
@@ -765,6 +787,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="bound on the oracle's CPU time for the batch workloads")
     ap.add_argument("--retune", action="store_true", help="ignore cached batch schedules")
+    ap.add_argument("--no-fuse", action="store_true",
+                    help="batches: keep the reconstruction and the finish of frames without EPF "
+                         "passes apart (XYB through memory), for comparison")
     ap.add_argument("--c5-rate", type=float, default=200.0, help="serving: arrivals per second")
     ap.add_argument("--c5-seconds", type=float, default=60.0, help="serving: arrival window")
     ap.add_argument("--c5-budget-gb", type=float, default=8.0, help="serving: HBM budget (GiB)")

@@ -150,7 +150,7 @@ typedef struct {
    * clamped to +-qco_interval_mul quantization steps (dequantization weight
    * times AcMul; for the LLF corner, each of its DC samples to
    * +-qco_interval_mul times that sample's DcQuantField), and transformed
-   * back.  The batch functions reject it (JXLR_E_PARAM). */
+   * back. */
   int32_t  qco;
   float    qco_interval_mul;  /* C.10 default 0.5; finite, >= 0 */
   /* AC prediction of Annex H (1) or not (0, the default; the draft's
@@ -161,35 +161,39 @@ typedef struct {
    * multiplier of C.4.1 itself), then I.2.7 at N = 4 gives each varblock's top 2cy x 2cx
    * coefficients, which are added (LLF corner excepted) after the chroma
    * from luma.  Needs io->ac_pred for jxlr_reconstruct (filled by
-   * jxlr_ac_prediction); jxlr_decode manages it.  The batch functions reject
-   * it (JXLR_E_PARAM). */
+   * jxlr_ac_prediction); jxlr_decode and the batch functions manage it. */
   int32_t  ac_prediction;
   /* Noise of K.5 (1; kNoise) or not (0, the default), after Gaborish: per
    * 256x256 group three pseudorandom channels (K.5.2; SplitMix64-seeded
    * XorShift128+, made by jxlr_noise_channels), their 5x5 Laplacian times
    * 0.22, modulated by the strengths the LUT gives at 14 (Y + X) and
-   * 14 (Y - X).  Needs io->noise_raw for jxlr_finish; jxlr_decode manages it.
-   * The batch functions reject it (JXLR_E_PARAM). */
+   * 14 (Y - X).  Needs io->noise_raw for jxlr_finish; jxlr_decode and the
+   * batch functions manage it. */
   int32_t  noise;
   float    noise_lut[16];     /* C.4.8: u(10) / 1024 each; finite */
   /* Patches of K.3: the number of placements in io->patch_place (0: none),
    * added between the EPF passes (and the quantization constraint) and
-   * Gaborish.  The batch functions reject them (JXLR_E_PARAM). */
+   * Gaborish. */
   int32_t  num_patches;
   /* Dots of K.2: the number of quantized dots in io->dots (0: none), added
    * after Gaborish (and before the noise); with dots, jxlr_finish skips its
    * Gaborish and the caller runs jxlr_gaborish then jxlr_dots before it
    * (jxlr_decode does).  dot_colour_quant: the draft's kColourQuant, which it
-   * does not give (finite).  The batch functions reject dots. */
+   * does not give (finite). */
   int32_t  num_dots;
   float    dot_colour_quant[3];
   /* Splines of K.4: the number of splines in io (0: none), rendered after
    * the dots (and before the noise); like dots they make Gaborish a pass of
    * its own.  num_spline_points: the control points of all of them (at
-   * least one each, at most 2^22 in all); it sizes the curve scratch.  The
-   * batch functions reject splines. */
+   * least one each, at most 2^22 in all); it sizes the curve scratch. */
   int32_t  num_splines;
   int32_t  num_spline_points;
+  /* The reconstruction fused with the finish (jxlr_reconstruct_finish) for a
+   * frame that qualifies (no EPF pass, patches, dots, splines or noise):
+   * 0 (the default) lets the library choose the tiles per run, 1..4 sets
+   * them, -1 keeps the two stages apart (jxlr_decode then stores the XYB
+   * frame in its workspace).  The output does not depend on it. */
+  int32_t  fuse;
 } jxlr_frame_params;
 
 /* Input and output planes of one frame.  With Wb = ceil(xsize/8),
@@ -434,6 +438,25 @@ jxlr_status jxlr_noise_channels(jxlr_ctx* ctx, const jxlr_frame_params* p, float
 jxlr_status jxlr_finish(jxlr_ctx* ctx, const jxlr_frame_params* p, const jxlr_frame_io* io,
                         const float* xyb, size_t xyb_stride, hipStream_t stream);
 
+/* The reconstruction (as jxlr_reconstruct) followed by the finish (as
+ * jxlr_finish) without an intermediate XYB frame, for a frame whose
+ * reconstruction goes to the finish unchanged: no EPF pass (C.10) and no
+ * patches, dots, splines or noise (Annex K).  Output into io->out in
+ * p->out_format, equal bit for bit to jxlr_reconstruct then jxlr_finish.
+ * Each workgroup reconstructs a run of tiles of one tile row into on-chip
+ * memory and finishes the pixels whose Gaborish window lies there; the
+ * samples along tile-row and run boundaries go to `seam` (device memory
+ * owned by the caller, at least jxlr_seam_bytes(p) bytes, overwritten), and
+ * a second launch on the same stream finishes the pixels on those
+ * boundaries.  Errors: JXLR_E_PARAM for a frame that does not qualify,
+ * JXLR_E_WORKSPACE for a seam buffer below jxlr_seam_bytes(p), and those of
+ * jxlr_reconstruct and jxlr_finish.  jxlr_decode takes this path for every
+ * frame that qualifies. */
+size_t jxlr_seam_bytes(const jxlr_frame_params* p); /* 0 if the frame does not qualify */
+jxlr_status jxlr_reconstruct_finish(jxlr_ctx* ctx, const jxlr_frame_params* p,
+                                    const jxlr_frame_io* io, const uint8_t* info, float* seam,
+                                    size_t seam_bytes, hipStream_t stream);
+
 /* ---- JPEG1 direct rasterization (M.6) ----------------------------------------
  * A recompressed JPEG1 frame (M.4 already decoded: quantized DCT coefficients
  * per component and the quantization tables) straight to RGB: dequantization
@@ -521,17 +544,21 @@ jxlr_status jxlr_jpeg1_decode(jxlr_ctx* ctx, const jxlr_jpeg1_params* p,
  * bit-identical to jxlr_decode of each frame alone. */
 
 /* Stages of a batch, for jxlr_batch_stage.  The tile stages INFO, RECON, EPF
- * and FINISH take every frame; the option stages PRED (Annex H, before
- * RECON), QCO (J.3, after the EPF passes), PATCHES (K.3), NOISE (K.5
- * channels), GABORISH (J.4 as its own pass, for frames with dots or
- * splines), DOTS (K.2) and SPLINES (K.4), in this order before FINISH, take
- * the frames that use them. */
+ * and FINISH take every frame (INFO) or every frame outside FUSED (the
+ * others); the option stages PRED (Annex H, before RECON), QCO (J.3, after
+ * the EPF passes), PATCHES (K.3), NOISE (K.5 channels), GABORISH (J.4 as
+ * its own pass, for frames with dots or splines), DOTS (K.2) and SPLINES
+ * (K.4), in this order before FINISH, take the frames that use them; FUSED
+ * and SEAM (after PRED) take the frames jxlr_reconstruct_finish qualifies
+ * (no EPF pass, patches, dots, splines or noise) and do for them what
+ * jxlr_reconstruct_finish does, reconstruction to output. */
 enum {
   JXLR_STAGE_INFO = 0, JXLR_STAGE_RECON = 1, JXLR_STAGE_EPF = 2, JXLR_STAGE_FINISH = 3,
   JXLR_STAGE_PRED = 4, JXLR_STAGE_QCO = 5, JXLR_STAGE_PATCHES = 6, JXLR_STAGE_NOISE = 7,
-  JXLR_STAGE_GABORISH = 8, JXLR_STAGE_DOTS = 9, JXLR_STAGE_SPLINES = 10
+  JXLR_STAGE_GABORISH = 8, JXLR_STAGE_DOTS = 9, JXLR_STAGE_SPLINES = 10,
+  JXLR_STAGE_FUSED = 11, JXLR_STAGE_SEAM = 12
 };
-#define JXLR_BATCH_OPT_STAGES 7 /* JXLR_STAGE_PRED .. JXLR_STAGE_SPLINES */
+#define JXLR_BATCH_OPT_STAGES 9 /* JXLR_STAGE_PRED .. JXLR_STAGE_SEAM */
 
 /* Device workspace for a batch: a descriptor header plus, per frame, what
  * jxlr_workspace_bytes(&p[i]) names; 0 if n <= 0 or a parameter set is out of
@@ -543,7 +570,7 @@ typedef struct jxlr_batch_plan {
   void* ws;
   size_t ws_bytes;
   int n;
-  int total_tiles;   /* 64x32 pixel tiles over all frames */
+  int total_tiles;   /* 64x32 pixel tiles over the frames outside FUSED */
   int total_regions; /* 32x32 DctSelect regions over all frames */
   int max_epf_iters;
   size_t frames_offset, tile_frame_offset, tile_start_offset, region_start_offset;
@@ -586,10 +613,10 @@ jxlr_status jxlr_batch_prepare(jxlr_ctx* ctx, int n, const jxlr_frame_params* p,
                                jxlr_batch_plan* plan, hipStream_t stream);
 
 /* Enqueues the whole path for every frame of the plan on `stream`: block
- * info, AC prediction, reconstruction, max_epf_iters EPF passes (a frame
- * with fewer passes sits out the rest), the option stages from QCO to
- * SPLINES, and finish; a stage that no frame takes launches nothing.  cfg
- * may be NULL. */
+ * info, AC prediction, the fused reconstruction and finish with its seam
+ * pass, reconstruction, max_epf_iters EPF passes (a frame with fewer passes
+ * sits out the rest), the option stages from QCO to SPLINES, and finish; a
+ * stage that no frame takes launches nothing.  cfg may be NULL. */
 jxlr_status jxlr_batch_run(jxlr_ctx* ctx, const jxlr_batch_plan* plan,
                            const jxlr_launch_config* cfg, hipStream_t stream);
 

@@ -39,6 +39,7 @@ struct jxlr_ctx {
   DeviceTables* tables;  // device memory
   int* status;           // device memory: [0] the sticky validation flag, [1] its last read
   void* scratch;         // this device's copy of `scratch` (jxlr_decode_noalloc)
+  int cus;               // compute units of the device
 };
 
 namespace {
@@ -701,12 +702,17 @@ __device__ __attribute__((always_inline)) inline void inverse_passes(
   __syncthreads();
 }
 
-// One 64x32 tile (tile column tbx, row tby) of the reconstruction.
+// One 64x32 tile (tile column tbx, row tby) of the reconstruction, up to the
+// tile's XYB samples in LDS; then epi(coef, s_bad) consumes them (coef:
+// channel, row, column of the tile; s_bad: per region, whether its DctSelect
+// entries were ill-formed, in which case its samples are not written and
+// count as zero).
 // SPLIT: the variant with the split-precision transform (taken for the
 // regions of frames whose a.split is set); the plain variant keeps the
 // register budget of the binary32 passes alone.
-template <bool SPLIT>
-__device__ __attribute__((always_inline)) inline void recon_tile(const ReconArgs& a, int tbx, int tby) {
+template <bool SPLIT, typename Epi>
+__device__ __attribute__((always_inline)) inline void recon_core(const ReconArgs& a, int tbx, int tby,
+                                                                 Epi&& epi) {
   __shared__ float coef[3][kRecTH][kRecLd];
   // DC samples per tile block (b = row * 8 + column), zero-padded so that a
   // fixed 4x4 window starting at any block stays inside the array.
@@ -720,7 +726,11 @@ __device__ __attribute__((always_inline)) inline void recon_tile(const ReconArgs
   // split-precision transform, or -1 for the binary32 passes
   __shared__ int s_mma[2];
 
-  const int tid = threadIdx.x;
+  // the thread index as a value recomputed where it is used: in the fused
+  // kernel's loop over the tiles of a run, addresses derived from it would
+  // otherwise be hoisted out of the loop and held in registers throughout
+  int tid = threadIdx.x;
+  asm volatile("" : "+v"(tid));
   const int wave = tid >> 6, lane = tid & 63;
   const int x0 = kRecTW * tbx, y0 = kRecTH * tby;
   const int gbx0 = x0 / 8, gby0 = y0 / 8;
@@ -902,10 +912,16 @@ __device__ __attribute__((always_inline)) inline void recon_tile(const ReconArgs
     }
     __syncthreads();
   }
+  epi(coef, s_bad);
+}
 
-  // Crop (6.2) and store, the thread's groups again; an ill-formed region is
-  // written as zero.
-  {
+// One tile of the reconstruction, stored to the XYB planes: crop (6.2), the
+// thread's 4-sample groups; an ill-formed region is written as zero.
+template <bool SPLIT>
+__device__ __attribute__((always_inline)) inline void recon_tile(const ReconArgs& a, int tbx, int tby) {
+  recon_core<SPLIT>(a, tbx, tby, [&](float (*coef)[kRecTH][kRecLd], const int* s_bad) {
+    const int tid = threadIdx.x;
+    const int x0 = kRecTW * tbx, y0 = kRecTH * tby;
 #pragma unroll
     for (int k = 0; k < kRecGPT; ++k) {
       const int g = tid + kRecThreads * k;
@@ -926,7 +942,7 @@ __device__ __attribute__((always_inline)) inline void recon_tile(const ReconArgs
         }
       }
     }
-  }
+  });
 }
 
 // ---------------------------------------------------------------------------
@@ -2021,6 +2037,19 @@ __device__ inline void noise_add(const FinishArgs& a, int x, int y, float (&v)[3
   v[2] = fmaf(0.935669f, nr + ng, v[2]);
 }
 
+// J.4 at one pixel from its 3x3 window: rows u (above), m and d (below),
+// each [channel][column: left, centre, right]; every path that applies
+// Gaborish before the colour transform goes through this one expression.
+__device__ inline void gab_pixel(const FinishArgs& a, const float (&u)[3][3], const float (&m)[3][3],
+                                 const float (&d)[3][3], float (&v)[3]) {
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const float e4 = (u[c][1] + m[c][0]) + (m[c][2] + d[c][1]);
+    const float cn = (u[c][0] + u[c][2]) + (d[c][0] + d[c][2]);
+    v[c] = fmaf(a.k0[c], m[c][1], fmaf(a.k1[c], e4, a.k2[c] * cn));
+  }
+}
+
 // Output rows per finish thread (ROWS); a 64x32 tile takes 64 * 32 / ROWS
 // threads.  The single-frame kernel uses 4 rows, the batch kernel 8 (fewer
 // re-read halo rows, measured faster over many small frames).
@@ -2104,12 +2133,7 @@ __device__ inline void finish_strip(const FinishArgs& a, const float* __restrict
     const int u = r % 3, m = (r + 1) % 3, d = (r + 2) % 3;
     load_row(r + 2, w[d]);
     float v[3];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      const float e4 = (w[u][c][1] + w[m][c][0]) + (w[m][c][2] + w[d][c][1]);
-      const float cn = (w[u][c][0] + w[u][c][2]) + (w[d][c][0] + w[d][c][2]);
-      v[c] = fmaf(a.k0[c], w[m][c][1], fmaf(a.k1[c], e4, a.k2[c] * cn));
-    }
+    gab_pixel(a, w[u], w[m], w[d], v);
     store(r, v);
   }
 }
@@ -2159,6 +2183,293 @@ __device__ __attribute__((always_inline)) inline void finish_tile(const FinishAr
   else
     JXLR_FINISH(JXLR_OUT_U16_SRGB, a.thr, nullptr);
 #undef JXLR_FINISH
+}
+
+// ---------------------------------------------------------------------------
+// Reconstruction fused with the finish.  When a frame's reconstruction goes
+// to the finish unchanged (no EPF pass, patches, dots, splines or noise),
+// its XYB samples need not pass through HBM: a workgroup takes a run of
+// consecutive tiles of one tile row, reconstructs each tile into LDS
+// (recon_core) and finishes there every pixel whose 3x3 Gaborish window,
+// after the 6.5 mirroring, lies inside the tile or in the last two columns
+// of the tile before it in the run (kept in LDS).  The remaining pixels are
+// the seams: the first / last row of a tile with another tile row above /
+// below it, and the first / last column of a run with another run beside
+// it.  A tile writes the two rows or columns of samples along each such side
+// into its seam record, and the seam pass finishes the seam pixels from the
+// records afterwards.  Every pixel goes through the finish kernel's
+// operations in the same order (gab_pixel, xyb_to_rgb, encode_out), so the
+// output equals that of the reconstruction followed by the finish bit for
+// bit.
+
+// Seam record of a tile: rows 0, 1, h - 2 and h - 1 of the tile, each
+// [3 channels][64 columns], then columns 0, 1, w - 2 and w - 1, each
+// [3][32 rows]; only the sides that face another tile row or run are written.
+constexpr int kSeamRowF = 3 * kRecTW;
+constexpr int kSeamColF = 3 * kRecTH;
+constexpr int kSeamTileF = 4 * kSeamRowF + 4 * kSeamColF;
+constexpr int kRunMax = 4;  // tiles per run at most
+constexpr int kSeamThreads = 256;
+// Rows of a tile per wave in the fused finish: three waves cover 32 rows.
+constexpr int kFusedRows = (kRecTH + kRecThreads / 64 - 1) / (kRecThreads / 64);
+
+struct FusedArgs {
+  ReconArgs rec;   // rec.xyb is not used
+  FinishArgs fin;  // fin.in is not used
+  float* seam;     // kSeamTileF floats per tile, tiles in row order
+  int tiles_x, tiles_y;
+  int run;         // tiles per run, 1 .. kRunMax
+  int runs_x;      // runs per tile row: ceil(tiles_x / run)
+};
+
+// The finish step of tile (tx, ty), the tile's samples in coef (and the
+// last two columns of the tile before it in carry, when it is not the first
+// of its run).  first / last: the tile starts / ends its run.
+template <int FMT>
+__device__ __attribute__((always_inline)) inline void fused_tile(
+    const FusedArgs& f, float (*coef)[kRecTH][kRecLd], const int* s_bad,
+    float (*carry)[kRecTH][2], int tx, int ty, bool first, bool last,
+    const float* __restrict__ thr, const uint8_t* __restrict__ start8) {
+  using T = typename OutT<FMT>::T;
+  const FinishArgs& a = f.fin;
+  int tid = threadIdx.x;  // recomputed per tile, as in recon_core
+  asm volatile("" : "+v"(tid));
+  const int lane = tid & 63, wave = tid >> 6;
+  const int x0 = kRecTW * tx, y0 = kRecTH * ty;
+  const int w = min(kRecTW, a.W - x0), h = min(kRecTH, a.H - y0);
+  // an ill-formed region's samples are zero, as the reconstruction stores them
+  if (s_bad[0] | s_bad[1]) {
+    for (int i = tid; i < 3 * kRecTH * kRecTW; i += kRecThreads) {
+      const int x = i & 63, y = (i >> 6) & 31, c = i >> 11;
+      if (s_bad[x >> 5]) coef[c][y][x] = 0.0f;
+    }
+    __syncthreads();
+  }
+  const bool up = ty > 0, down = ty + 1 < f.tiles_y;
+  const bool left = first && tx > 0, right = last && tx + 1 < f.tiles_x;
+  float* rec = f.seam + (size_t(ty) * f.tiles_x + tx) * kSeamTileF;
+  if (up || down) {
+    for (int i = tid; i < 4 * kSeamRowF; i += kRecThreads) {
+      const int r = i / kSeamRowF, c = (i >> 6) % 3, x = i & 63;
+      const int y = r < 2 ? r : h - 4 + r;
+      if ((r < 2 ? up : down) && x < w && y >= 0 && y < h) rec[i] = coef[c][y][x];
+    }
+  }
+  if (left || right) {
+    for (int i = tid; i < 4 * kSeamColF; i += kRecThreads) {
+      const int q = i / kSeamColF, c = (i >> 5) % 3, y = i & 31;
+      const int x = q < 2 ? q : w - 4 + q;
+      if ((q < 2 ? left : right) && y < h && x >= 0 && x < w)
+        rec[4 * kSeamRowF + i] = coef[c][y][x];
+    }
+  }
+
+  // Lane l finishes column x0 - 1 + l: lane 0 the last column of the tile
+  // before (whose right neighbour is this tile's first column), lanes 1 ..
+  // w - 1 this tile's columns but its last, lane w its last column when the
+  // frame ends there (mirrored back into the tile).  The first column of a
+  // run with another run to its left is a seam.
+  const int gx = x0 - 1 + lane;
+  bool col;
+  if (lane == 0) col = !first;
+  else if (lane == 1 && left) col = false;
+  else if (lane < w) col = true;
+  else col = lane == w && tx + 1 == f.tiles_x;
+  // the three window columns: tile columns >= 0 from coef, -2 and -1 from
+  // carry (clamped into the arrays for lanes that store nothing)
+  const float* src[3];
+  int ld[3];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    const int xj = min(max(mirror(gx - 1 + j, a.W) - x0, -2), kRecTW - 1);
+    src[j] = xj >= 0 ? &coef[0][0][xj] : &carry[0][0][xj + 2];
+    ld[j] = xj >= 0 ? kRecLd : 2;
+  }
+  auto rowidx = [&](int r) { return min(max(mirror(y0 + r, a.H) - y0, 0), h - 1); };
+  auto load_row = [&](int r, float (&wv)[3][3]) {
+    const int yy = rowidx(r);
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) wv[c][j] = src[j][(c * kRecTH + yy) * ld[j]];
+  };
+  T* out[3] = {static_cast<T*>(a.out[0]), static_cast<T*>(a.out[1]), static_cast<T*>(a.out[2])};
+  auto finish_px = [&](int x, int r, const float (&u)[3][3], const float (&m)[3][3],
+                       const float (&d)[3][3]) {
+    float v[3];
+    if (a.gab) {
+      gab_pixel(a, u, m, d, v);
+    } else {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) v[c] = m[c][1];
+    }
+    float rgb[3];
+    xyb_to_rgb(a, v, rgb);
+    const size_t o = size_t(y0 + r) * a.out_stride + x;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) out[c][o] = encode_out<FMT>(rgb[c], thr, start8);
+  };
+  // rows that are seams
+  auto seam_row = [&](int r) { return (r == 0 && up) || (r == h - 1 && down); };
+  {
+    const int r0 = kFusedRows * wave, r1 = min(r0 + kFusedRows, h);
+    float wu[3][3], wm[3][3], wd[3][3];  // window rows above, at and below row r
+    load_row(r0 - 1, wu);
+    load_row(r0, wm);
+#pragma unroll 1
+    for (int r = r0; r < r1; ++r) {
+      load_row(r + 1, wd);
+      if (col && !seam_row(r)) finish_px(gx, r, wu, wm, wd);
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+          wu[c][j] = wm[c][j];
+          wm[c][j] = wd[c][j];
+        }
+    }
+  }
+  // the frame's last column when the tile is 64 wide (no lane 64): thread r
+  // takes row r, window columns 62, 63 and 63 mirrored
+  if (w == kRecTW && tx + 1 == f.tiles_x && tid < h && !seam_row(tid)) {
+    float wv[3][3][3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const int yy = rowidx(tid - 1 + k);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        wv[k][c][0] = coef[c][yy][kRecTW - 2];
+        wv[k][c][1] = coef[c][yy][kRecTW - 1];
+        wv[k][c][2] = coef[c][yy][kRecTW - 1];
+      }
+    }
+    finish_px(x0 + kRecTW - 1, tid, wv[0], wv[1], wv[2]);
+  }
+  if (!last) {
+    __syncthreads();  // every read of carry for this tile is done
+    for (int i = tid; i < 3 * kRecTH * 2; i += kRecThreads) {
+      const int k = i & 1, y = (i >> 1) & 31, c = i >> 6;
+      carry[c][y][k] = coef[c][y][kRecTW - 2 + k];
+    }
+  }
+}
+
+// Run u of a frame (runs in row order, f.runs_x per tile row), in the
+// frame's output format; the 8-bit code tables are staged in LDS.  (One
+// recon_core instantiation for all formats: each holds its own LDS arrays.)
+template <bool SPLIT>
+__device__ __attribute__((always_inline)) inline void fused_unit(const FusedArgs& f, int u) {
+  __shared__ float carry[3][kRecTH][2];
+  __shared__ float s_thr[257];
+  __shared__ uint32_t s_start[kSrgbBucketsPadded / 4];
+  const int fmt = f.fin.format;
+  if (fmt == JXLR_OUT_U8_SRGB) {
+    for (int i = threadIdx.x; i < 257; i += kRecThreads) s_thr[i] = f.fin.thr[i];
+    for (int i = threadIdx.x; i < kSrgbBucketsPadded / 4; i += kRecThreads)
+      s_start[i] = reinterpret_cast<const uint32_t*>(f.fin.start8)[i];
+    // (recon_core's first barrier orders these stores before any read)
+  }
+  const uint8_t* start8 = reinterpret_cast<const uint8_t*>(s_start);
+  const int ty = u / f.runs_x, tx0 = (u - ty * f.runs_x) * f.run;
+  const int tx1 = min(tx0 + f.run, f.tiles_x);
+  for (int tx = tx0; tx < tx1; ++tx) {
+    if (tx > tx0) __syncthreads();  // the previous tile's reads of LDS are done
+    recon_core<SPLIT>(f.rec, tx, ty, [&](float (*coef)[kRecTH][kRecLd], const int* s_bad) {
+      const bool first = tx == tx0, last = tx + 1 == tx1;
+      if (fmt == JXLR_OUT_F32)
+        fused_tile<JXLR_OUT_F32>(f, coef, s_bad, carry, tx, ty, first, last, nullptr, nullptr);
+      else if (fmt == JXLR_OUT_U8_SRGB)
+        fused_tile<JXLR_OUT_U8_SRGB>(f, coef, s_bad, carry, tx, ty, first, last, s_thr, start8);
+      else
+        fused_tile<JXLR_OUT_U16_SRGB>(f, coef, s_bad, carry, tx, ty, first, last, f.fin.thr,
+                                      nullptr);
+    });
+  }
+}
+
+// Sample (channel c, column gx, row gy) from the seam records; the position
+// is one that some seam pixel's window needs (see fused_tile).
+__device__ inline float seam_sample(const FusedArgs& f, int c, int gx, int gy) {
+  const int tx = gx / kRecTW, ty = gy / kRecTH, lx = gx - kRecTW * tx, ly = gy - kRecTH * ty;
+  const int w = min(kRecTW, f.fin.W - kRecTW * tx), h = min(kRecTH, f.fin.H - kRecTH * ty);
+  const float* rec = f.seam + (size_t(ty) * f.tiles_x + tx) * kSeamTileF;
+  if (ly <= 1 && ty > 0) return rec[ly * kSeamRowF + c * kRecTW + lx];
+  if (ly >= h - 2 && ty + 1 < f.tiles_y) return rec[(ly - h + 4) * kSeamRowF + c * kRecTW + lx];
+  if (lx <= 1) return rec[4 * kSeamRowF + lx * kSeamColF + c * kRecTH + ly];
+  return rec[4 * kSeamRowF + (lx - w + 4) * kSeamColF + c * kRecTH + ly];
+}
+
+// The seam pixels of run u: its top and bottom rows where another tile row
+// is there, and its first / last column (rows between those) where another
+// run is there.
+template <int FMT>
+__device__ inline void seam_pixels(const FusedArgs& f, int u, const float* __restrict__ thr,
+                                   const uint8_t* __restrict__ start8) {
+  using T = typename OutT<FMT>::T;
+  const FinishArgs& a = f.fin;
+  const int ty = u / f.runs_x, tr = u - ty * f.runs_x;
+  const int X0 = kRecTW * f.run * tr, X1 = min(X0 + kRecTW * f.run, a.W);
+  const int y0 = kRecTH * ty, h = min(kRecTH, a.H - y0);
+  const bool up = ty > 0, down = ty + 1 < f.tiles_y;
+  const int ntop = up ? X1 - X0 : 0, nbot = down ? X1 - X0 : 0;
+  const int ya = up ? 1 : 0, yb = down ? h - 1 : h;
+  const int ncol = max(yb - ya, 0);
+  const int nl = X0 > 0 ? ncol : 0, nr = X1 < a.W ? ncol : 0;
+  const int total = ntop + nbot + nl + nr;
+  for (int i = threadIdx.x; i < total; i += kSeamThreads) {
+    int gx, gy;
+    if (i < ntop) {
+      gx = X0 + i;
+      gy = y0;
+    } else if (i < ntop + nbot) {
+      gx = X0 + (i - ntop);
+      gy = y0 + h - 1;
+    } else if (i < ntop + nbot + nl) {
+      gx = X0;
+      gy = y0 + ya + (i - ntop - nbot);
+    } else {
+      gx = X1 - 1;
+      gy = y0 + ya + (i - ntop - nbot - nl);
+    }
+    const int xs[3] = {mirror(gx - 1, a.W), gx, mirror(gx + 1, a.W)};
+    const int ys[3] = {mirror(gy - 1, a.H), gy, mirror(gy + 1, a.H)};
+    float wv[3][3][3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) wv[k][c][j] = seam_sample(f, c, xs[j], ys[k]);
+    float v[3];
+    if (a.gab) {
+      gab_pixel(a, wv[0], wv[1], wv[2], v);
+    } else {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) v[c] = wv[1][c][1];
+    }
+    float rgb[3];
+    xyb_to_rgb(a, v, rgb);
+    const size_t o = size_t(gy) * a.out_stride + gx;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) static_cast<T*>(a.out[c])[o] = encode_out<FMT>(rgb[c], thr, start8);
+  }
+}
+
+__device__ __attribute__((always_inline)) inline void seam_unit(const FusedArgs& f, int u) {
+  __shared__ float s_thr[257];
+  __shared__ uint32_t s_start[kSrgbBucketsPadded / 4];
+  const int fmt = f.fin.format;
+  if (fmt == JXLR_OUT_F32) {
+    seam_pixels<JXLR_OUT_F32>(f, u, nullptr, nullptr);
+  } else if (fmt == JXLR_OUT_U8_SRGB) {
+    for (int i = threadIdx.x; i < 257; i += kSeamThreads) s_thr[i] = f.fin.thr[i];
+    for (int i = threadIdx.x; i < kSrgbBucketsPadded / 4; i += kSeamThreads)
+      s_start[i] = reinterpret_cast<const uint32_t*>(f.fin.start8)[i];
+    __syncthreads();
+    seam_pixels<JXLR_OUT_U8_SRGB>(f, u, s_thr, reinterpret_cast<const uint8_t*>(s_start));
+  } else {
+    seam_pixels<JXLR_OUT_U16_SRGB>(f, u, f.fin.thr, nullptr);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -3075,6 +3386,29 @@ __global__ __launch_bounds__(kSplineThreads) void spline_batch_kernel(OptBatch o
   spline_one(a, opt_unit(ob, a, row));
 }
 
+// Reconstruction fused with the finish, and the seam pass after it: one
+// workgroup per run of tiles (FusedArgs); single-frame and batch forms.
+template <bool SPLIT>
+__global__ __launch_bounds__(kRecThreads, kRecMinBlocks) void fused_kernel(FusedArgs f) {
+  fused_unit<SPLIT>(f, xcd_tile(blockIdx.x, gridDim.x));
+}
+__global__ __launch_bounds__(kSeamThreads) void seam_kernel(FusedArgs f) {
+  seam_unit(f, blockIdx.x);
+}
+template <bool SPLIT>
+__global__ __launch_bounds__(kRecThreads, kRecMinBlocks) void fused_batch_kernel(OptBatch ob) {
+  __shared__ FusedArgs s_args;
+  int row;
+  const int u = opt_unit_lds(ob, s_args, row);
+  fused_unit<SPLIT>(s_args, u);
+}
+__global__ __launch_bounds__(kSeamThreads) void seam_batch_kernel(OptBatch ob) {
+  __shared__ FusedArgs s_args;
+  int row;
+  const int u = opt_unit_lds(ob, s_args, row);
+  seam_unit(s_args, u);
+}
+
 // ---------------------------------------------------------------------------
 // Host side.
 
@@ -3111,6 +3445,7 @@ jxlr_status check_params(const jxlr_frame_params* p) {
   if (p->ac_prediction < 0 || p->ac_prediction > 1) return JXLR_E_PARAM;
   if (p->noise < 0 || p->noise > 1) return JXLR_E_PARAM;
   if (p->num_patches < 0 || p->num_dots < 0) return JXLR_E_PARAM;
+  if (p->fuse < -1 || p->fuse > kRunMax) return JXLR_E_PARAM;
   if (p->num_splines < 0 || p->num_spline_points < 0 || p->num_spline_points > (1 << 22) ||
       (p->num_splines > 0 && p->num_spline_points < p->num_splines))
     return JXLR_E_PARAM;
@@ -3264,9 +3599,11 @@ jxlr_status jxlr_create(jxlr_ctx** out, int device, const jxlr_dequant_encoding*
     delete host;
     return JXLR_E_HIP;
   }
-  auto* ctx = new jxlr_ctx{device, nullptr, nullptr, nullptr};
+  auto* ctx = new jxlr_ctx{device, nullptr, nullptr, nullptr, 0};
   // this device's copy of the scratch array (the device is current here)
   hipError_t e = hipGetSymbolAddress(&ctx->scratch, HIP_SYMBOL(scratch));
+  if (e == hipSuccess)
+    e = hipDeviceGetAttribute(&ctx->cus, hipDeviceAttributeMultiprocessorCount, device);
   if (e == hipSuccess) e = hipMalloc(&ctx->tables, sizeof(DeviceTables));
   if (e == hipSuccess) e = hipMalloc(&ctx->status, 2 * sizeof(int));
   if (e == hipSuccess) e = hipMemcpy(ctx->tables, host, sizeof(DeviceTables), hipMemcpyHostToDevice);
@@ -3320,6 +3657,22 @@ jxlr_status jxlr_validate_maps_host(const jxlr_frame_params* p, const uint8_t* s
 
 namespace {
 size_t round256(size_t v) { return (v + 255) & ~size_t(255); }
+int tiles_x(const jxlr_frame_params* p) { return int((p->xsize + kRecTW - 1) / kRecTW); }
+int tiles_y(const jxlr_frame_params* p) { return int((p->ysize + kRecTH - 1) / kRecTH); }
+int regions_of(const jxlr_frame_params* p) {
+  return ((blocks_of(p->xsize) + 3) / 4) * ((blocks_of(p->ysize) + 3) / 4);
+}
+// Whether the frame's reconstruction goes to the finish unchanged (no EPF
+// pass and none of patches, dots, splines, noise), so that the fused kernel
+// takes both and no XYB frame is stored.
+bool fused_path(const jxlr_frame_params* p) {
+  return p->fuse >= 0 && p->epf_iters == 0 && !p->noise && p->num_patches == 0 &&
+         p->num_dots == 0 && p->num_splines == 0;
+}
+// Seam records of the fused path: one per tile.
+size_t seam_bytes(const jxlr_frame_params* p) {
+  return round256(size_t(tiles_x(p)) * tiles_y(p) * kSeamTileF * sizeof(float));
+}
 size_t info_bytes(const jxlr_frame_params* p) {
   return round256(size_t(blocks_of(p->xsize)) * blocks_of(p->ysize));
 }
@@ -3330,6 +3683,7 @@ size_t xyb_bytes(const jxlr_frame_params* p) {
 // alternating over one more buffer, or two more when the quantization
 // constraint needs the reconstruction kept past a second pass.
 int xyb_buffers(const jxlr_frame_params* p) {
+  if (fused_path(p)) return 0;
   if (p->epf_iters == 0) return 1;
   return p->qco && p->epf_iters > 1 ? 3 : 2;
 }
@@ -3365,12 +3719,14 @@ struct FrameBuffers {
   float* epf_out[3];
   float* post;    // after the EPF passes and the constraint; patches go here
   float* fin;     // what the finish reads: post, or gab
+  float* seam;    // seam records of the fused path (no XYB buffer then), or null
 };
 
 // Bytes of the layout frame_buffers lays out.
 size_t frame_ws_bytes(const jxlr_frame_params* p) {
   return info_bytes(p) + xyb_buffers(p) * xyb_bytes(p) + pred_bytes(p) +
-         (p->noise ? xyb_bytes(p) : 0) + (gab_pass(p) ? xyb_bytes(p) : 0) + spline_bytes(p);
+         (p->noise ? xyb_bytes(p) : 0) + (gab_pass(p) ? xyb_bytes(p) : 0) + spline_bytes(p) +
+         (fused_path(p) ? seam_bytes(p) : 0);
 }
 
 FrameBuffers frame_buffers(const jxlr_frame_params* p, char* base) {
@@ -3388,7 +3744,11 @@ FrameBuffers frame_buffers(const jxlr_frame_params* p, char* base) {
     b.gab = reinterpret_cast<float*>(t);
     t += xyb_bytes(p);
   }
-  if (p->num_splines > 0) b.spline = t;
+  if (p->num_splines > 0) {
+    b.spline = t;
+    t += spline_bytes(p);
+  }
+  if (fused_path(p)) b.seam = reinterpret_cast<float*>(t);
   const bool qco = p->qco && p->epf_iters > 0;
   float* cur = b.buf[0];
   for (int it = 0; it < p->epf_iters; ++it) {
@@ -3413,6 +3773,11 @@ size_t jxlr_workspace_bytes(const jxlr_frame_params* p) {
 size_t jxlr_spline_scratch_bytes(const jxlr_frame_params* p) {
   if (check_params(p) != JXLR_OK) return 0;
   return spline_bytes(p);
+}
+
+size_t jxlr_seam_bytes(const jxlr_frame_params* p) {
+  if (check_params(p) != JXLR_OK || !fused_path(p)) return 0;
+  return seam_bytes(p);
 }
 
 }  // extern "C"
@@ -3584,11 +3949,35 @@ jxlr_status make_finish_args(jxlr_ctx* ctx, const jxlr_frame_params* p, const jx
   return JXLR_OK;
 }
 
-int tiles_x(const jxlr_frame_params* p) { return int((p->xsize + kRecTW - 1) / kRecTW); }
-int tiles_y(const jxlr_frame_params* p) { return int((p->ysize + kRecTH - 1) / kRecTH); }
-int regions_of(const jxlr_frame_params* p) {
-  return ((blocks_of(p->xsize) + 3) / 4) * ((blocks_of(p->ysize) + 3) / 4);
+// Tiles per run of the fused path: longer runs (fewer seams) while the
+// units still fill the device about twice over.
+int fused_run_length(const jxlr_ctx* ctx, long long tiles) {
+  const long long fill = 2LL * std::max(ctx->cus, 1) * kRecMinBlocks;
+  return int(std::max(1LL, std::min<long long>(kRunMax, tiles / fill)));
 }
+
+jxlr_status make_fused_args(jxlr_ctx* ctx, const jxlr_frame_params* p, const jxlr_frame_io* io,
+                            const uint8_t* info, float* seam, size_t seam_len, int run,
+                            FusedArgs* res) {
+  if (!fused_path(p)) return JXLR_E_PARAM;
+  if (!seam) return JXLR_E_NULL;
+  if (seam_len < seam_bytes(p)) return JXLR_E_WORKSPACE;
+  if (run < 1 || run > kRunMax) return JXLR_E_PARAM;
+  FusedArgs f{};
+  // the reconstruction's arguments name the seam records as its (unused)
+  // XYB buffer
+  jxlr_status st = make_recon_args(ctx, p, io, info, seam, p->xsize, &f.rec);
+  if (!st) st = make_finish_args(ctx, p, io, nullptr, p->xsize, &f.fin);
+  if (st) return st;
+  f.seam = seam;
+  f.tiles_x = tiles_x(p);
+  f.tiles_y = tiles_y(p);
+  f.run = run;
+  f.runs_x = (f.tiles_x + run - 1) / run;
+  *res = f;
+  return JXLR_OK;
+}
+
 
 }  // namespace
 
@@ -3912,6 +4301,26 @@ jxlr_status jxlr_finish(jxlr_ctx* ctx, const jxlr_frame_params* p, const jxlr_fr
   return launch_status(hipGetLastError());
 }
 
+jxlr_status jxlr_reconstruct_finish(jxlr_ctx* ctx, const jxlr_frame_params* p,
+                                    const jxlr_frame_io* io, const uint8_t* info, float* seam,
+                                    size_t seam_len, hipStream_t stream) {
+  if (!ctx) return JXLR_E_NULL;
+  jxlr_status st = check_params(p);
+  if (st) return st;
+  FusedArgs f;
+  const int run = p->fuse > 0 ? p->fuse : fused_run_length(ctx, (long long)tiles_x(p) * tiles_y(p));
+  if ((st = make_fused_args(ctx, p, io, info, seam, seam_len, run, &f))) return st;
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return JXLR_E_HIP;
+  const dim3 grid(f.runs_x * f.tiles_y);
+  if (p->idct_split)
+    hipLaunchKernelGGL(fused_kernel<true>, grid, dim3(kRecThreads), 0, stream, f);
+  else
+    hipLaunchKernelGGL(fused_kernel<false>, grid, dim3(kRecThreads), 0, stream, f);
+  if (grid.x > 1) hipLaunchKernelGGL(seam_kernel, grid, dim3(kSeamThreads), 0, stream, f);
+  return launch_status(hipGetLastError());
+}
+
 jxlr_status jxlr_decode(jxlr_ctx* ctx, const jxlr_frame_params* p, const jxlr_frame_io* io,
                         void* ws, size_t ws_bytes, hipStream_t stream) {
   if (!ctx || !io || !ws) return JXLR_E_NULL;
@@ -3926,6 +4335,8 @@ jxlr_status jxlr_decode(jxlr_ctx* ctx, const jxlr_frame_params* p, const jxlr_fr
   iop.noise_raw = b.noise;
   if ((st = jxlr_block_info(ctx, p, io, b.info, stream))) return st;
   if (p->ac_prediction && (st = jxlr_ac_prediction(ctx, p, io, b.info, b.pred, stream))) return st;
+  if (fused_path(p))
+    return jxlr_reconstruct_finish(ctx, p, &iop, b.info, b.seam, seam_bytes(p), stream);
   if ((st = jxlr_reconstruct(ctx, p, &iop, b.info, b.buf[0], stride, stream))) return st;
   for (int it = 0; it < p->epf_iters; ++it)
     if ((st = jxlr_epf_pass(ctx, p, io, b.info, b.epf_in[it], b.epf_out[it], stride, nullptr,
@@ -4156,7 +4567,7 @@ jxlr_status jxlr_jpeg1_decode(jxlr_ctx* ctx, const jxlr_jpeg1_params* p,
 
 namespace {
 constexpr int kOptStages = JXLR_BATCH_OPT_STAGES;
-static_assert(JXLR_STAGE_SPLINES - JXLR_STAGE_PRED + 1 == kOptStages, "option stage numbering");
+static_assert(JXLR_STAGE_SEAM - JXLR_STAGE_PRED + 1 == kOptStages, "option stage numbering");
 
 // Whether frame p takes option stage k (JXLR_STAGE_PRED + k), as the
 // single-frame decode does.
@@ -4169,6 +4580,8 @@ bool takes_opt(const jxlr_frame_params* p, int k) {
     case JXLR_STAGE_GABORISH: return gab_pass(p);
     case JXLR_STAGE_DOTS: return p->num_dots > 0;
     case JXLR_STAGE_SPLINES: return p->num_splines > 0;
+    case JXLR_STAGE_FUSED:
+    case JXLR_STAGE_SEAM: return fused_path(p);
   }
   return false;
 }
@@ -4182,6 +4595,8 @@ size_t opt_entry_bytes(int k) {
     case JXLR_STAGE_GABORISH: return sizeof(OptEntry<GabArgs>);
     case JXLR_STAGE_DOTS: return sizeof(OptEntry<DotArgs>);
     case JXLR_STAGE_SPLINES: return sizeof(OptEntry<SplineArgs>);
+    case JXLR_STAGE_FUSED:
+    case JXLR_STAGE_SEAM: return sizeof(OptEntry<FusedArgs>);
   }
   return 0;
 }
@@ -4199,7 +4614,8 @@ struct BatchLayout {
 BatchLayout batch_layout(int n, const jxlr_frame_params* p) {
   BatchLayout L;
   size_t tiles = 0;
-  for (int i = 0; i < n; ++i) tiles += size_t(tiles_x(&p[i])) * tiles_y(&p[i]);
+  for (int i = 0; i < n; ++i)
+    if (!fused_path(&p[i])) tiles += size_t(tiles_x(&p[i])) * tiles_y(&p[i]);
   L.frames = 0;
   L.tile_frame = round256(sizeof(FrameDesc) * size_t(n));
   L.tile_start = L.tile_frame + round256(sizeof(int) * tiles);
@@ -4225,7 +4641,7 @@ BatchLayout batch_layout(int n, const jxlr_frame_params* p) {
 
 jxlr_status check_plan(jxlr_ctx* ctx, const jxlr_batch_plan* plan) {
   if (!ctx || !plan || !plan->ws) return JXLR_E_NULL;
-  if (plan->n <= 0 || plan->total_tiles <= 0 || plan->total_regions <= 0 ||
+  if (plan->n <= 0 || plan->total_tiles < 0 || plan->total_regions <= 0 ||
       plan->max_epf_iters < 0 || plan->max_epf_iters > 3)
     return JXLR_E_SIZE;
   for (int k = 0; k < kOptStages; ++k)
@@ -4271,6 +4687,15 @@ jxlr_status launch_stage(jxlr_ctx* ctx, const jxlr_batch_plan* plan, int stage, 
       case JXLR_STAGE_SPLINES:
         hipLaunchKernelGGL(spline_batch_kernel, g, dim3(kSplineThreads), 0, stream, ob);
         break;
+      case JXLR_STAGE_FUSED:
+        if (plan->any_split)
+          hipLaunchKernelGGL(fused_batch_kernel<true>, g, dim3(kRecThreads), 0, stream, ob);
+        else
+          hipLaunchKernelGGL(fused_batch_kernel<false>, g, dim3(kRecThreads), 0, stream, ob);
+        break;
+      case JXLR_STAGE_SEAM:
+        hipLaunchKernelGGL(seam_batch_kernel, g, dim3(kSeamThreads), 0, stream, ob);
+        break;
       default:
         return JXLR_E_PARAM;
     }
@@ -4285,6 +4710,7 @@ jxlr_status launch_stage(jxlr_ctx* ctx, const jxlr_batch_plan* plan, int stage, 
   b.pass = epf_pass;
   const int full = stage == JXLR_STAGE_INFO ? (plan->total_regions + kInfoThreads - 1) / kInfoThreads
                                             : plan->total_tiles;
+  if (full == 0) return JXLR_OK;  // every frame takes the fused stages
   int gsz = grid > 0 ? std::min(grid, full) : full;
   b.order = order == 1 ? 1 : 0;
   const bool persist = gsz < full;
@@ -4356,6 +4782,11 @@ jxlr_status jxlr_batch_prepare(jxlr_ctx* ctx, int n, const jxlr_frame_params* p,
   std::vector<int> ostart[kOptStages];
   for (int k = 0; k < kOptStages; ++k) ostart[k].push_back(0);
   int max_epf = 0, any_noise = 0;
+  // one run length over the batch's fused frames
+  long long fused_tiles = 0;
+  for (int i = 0; i < n; ++i)
+    if (fused_path(&p[i])) fused_tiles += (long long)tiles_x(&p[i]) * tiles_y(&p[i]);
+  const int run = fused_run_length(ctx, fused_tiles);
   for (int i = 0; i < n; ++i) {
     FrameDesc& d = frames[i];
     const FrameBuffers fb = frame_buffers(&p[i], base + L.frame_off[i]);
@@ -4363,12 +4794,14 @@ jxlr_status jxlr_batch_prepare(jxlr_ctx* ctx, int n, const jxlr_frame_params* p,
     iop.ac_pred = fb.pred;
     iop.noise_raw = fb.noise;
     const size_t stride = p[i].xsize;
+    const bool fused = fused_path(&p[i]);
     jxlr_status st = make_info_args(ctx, &p[i], &iop, fb.info, &d.info);
-    if (!st) st = make_recon_args(ctx, &p[i], &iop, fb.info, fb.buf[0], stride, &d.rec);
+    // (a fused frame's tile stage arguments are not used)
+    if (!st && !fused) st = make_recon_args(ctx, &p[i], &iop, fb.info, fb.buf[0], stride, &d.rec);
     for (int k = 0; k < p[i].epf_iters && !st; ++k)
       st = make_epf_args(ctx, &p[i], &iop, fb.info, fb.epf_in[k], fb.epf_out[k], stride, nullptr,
                          nullptr, &d.epf[k]);
-    if (!st) st = make_finish_args(ctx, &p[i], &iop, fb.fin, stride, &d.fin);
+    if (!st && !fused) st = make_finish_args(ctx, &p[i], &iop, fb.fin, stride, &d.fin);
     // option stages, in the order of the single-frame decode
     for (int k = 0; k < kOptStages && !st; ++k) {
       if (!takes_opt(&p[i], k)) continue;
@@ -4419,6 +4852,16 @@ jxlr_status jxlr_batch_prepare(jxlr_ctx* ctx, int n, const jxlr_frame_params* p,
             put_entry(hdr, at, a, 0);
           break;
         }
+        case JXLR_STAGE_FUSED:
+        case JXLR_STAGE_SEAM: {
+          FusedArgs a;
+          if (!(st = make_fused_args(ctx, &p[i], &iop, fb.info, fb.seam, seam_bytes(&p[i]),
+                                     p[i].fuse > 0 ? p[i].fuse : run, &a))) {
+            put_entry(hdr, at, a, a.runs_x);
+            units = a.runs_x * a.tiles_y;
+          }
+          break;
+        }
       }
       const long long nu = (long long)ostart[k].back() + units;
       if (!st && nu > INT32_MAX / 2) st = JXLR_E_SIZE;
@@ -4427,7 +4870,7 @@ jxlr_status jxlr_batch_prepare(jxlr_ctx* ctx, int n, const jxlr_frame_params* p,
     if (st) return st;
     d.epf_iters = p[i].epf_iters;
     d.tiles_x = tiles_x(&p[i]);
-    const long long nt = (long long)tstart[i] + tiles_x(&p[i]) * tiles_y(&p[i]);
+    const long long nt = (long long)tstart[i] + (fused ? 0 : tiles_x(&p[i]) * tiles_y(&p[i]));
     if (nt > INT32_MAX / 2) return JXLR_E_SIZE;
     tstart[i + 1] = int(nt);
     tframe.resize(tstart[i + 1], i);
@@ -4436,7 +4879,8 @@ jxlr_status jxlr_batch_prepare(jxlr_ctx* ctx, int n, const jxlr_frame_params* p,
     any_noise |= p[i].noise;
   }
   std::memcpy(hdr.data() + L.frames, frames.data(), sizeof(FrameDesc) * n);
-  std::memcpy(hdr.data() + L.tile_frame, tframe.data(), sizeof(int) * tframe.size());
+  if (!tframe.empty())
+    std::memcpy(hdr.data() + L.tile_frame, tframe.data(), sizeof(int) * tframe.size());
   std::memcpy(hdr.data() + L.tile_start, tstart.data(), sizeof(int) * (n + 1));
   std::memcpy(hdr.data() + L.region_start, rstart.data(), sizeof(int) * (n + 1));
   for (int k = 0; k < kOptStages; ++k)
@@ -4480,6 +4924,8 @@ jxlr_status jxlr_batch_run(jxlr_ctx* ctx, const jxlr_batch_plan* plan,
   const jxlr_launch_config c = cfg ? *cfg : jxlr_launch_config{};
   if ((st = launch_stage(ctx, plan, JXLR_STAGE_INFO, c.grid_info, 0, 0, stream))) return st;
   if ((st = launch_stage(ctx, plan, JXLR_STAGE_PRED, 0, 0, 0, stream))) return st;
+  if ((st = launch_stage(ctx, plan, JXLR_STAGE_FUSED, 0, 0, 0, stream))) return st;
+  if ((st = launch_stage(ctx, plan, JXLR_STAGE_SEAM, 0, 0, 0, stream))) return st;
   if ((st = launch_stage(ctx, plan, JXLR_STAGE_RECON, c.grid_recon, c.order_recon, 0, stream)))
     return st;
   for (int k = 0; k < plan->max_epf_iters; ++k)
@@ -4494,7 +4940,7 @@ jxlr_status jxlr_batch_stage(jxlr_ctx* ctx, const jxlr_batch_plan* plan, int sta
                              int order, int epf_pass, hipStream_t stream) {
   jxlr_status st = check_plan(ctx, plan);
   if (st) return st;
-  if (stage < 0 || stage > JXLR_STAGE_SPLINES || order < 0 || order > 1 || epf_pass < 0 ||
+  if (stage < 0 || stage > JXLR_STAGE_SEAM || order < 0 || order > 1 || epf_pass < 0 ||
       (stage == JXLR_STAGE_EPF && epf_pass >= plan->max_epf_iters))
     return JXLR_E_PARAM;
   DeviceGuard g(ctx->device);
@@ -4535,7 +4981,8 @@ jxlr_status jxlr_autotune(jxlr_ctx* ctx, const jxlr_batch_plan* plan, int reps,
   jxlr_launch_config out{};
   float total_ms = 0.0f;
   for (int si = 0; si < 3 && !st; ++si) {
-    if (stages[si] == JXLR_STAGE_EPF && plan->max_epf_iters == 0) continue;
+    if (plan->total_tiles == 0 || (stages[si] == JXLR_STAGE_EPF && plan->max_epf_iters == 0))
+      continue;
     int occ = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kerns[si], threads[si], 0) !=
             hipSuccess || occ <= 0)

@@ -51,6 +51,7 @@ class FrameParams(C.Structure):
         ("dot_colour_quant", C.c_float * 3),
         ("num_splines", C.c_int32),
         ("num_spline_points", C.c_int32),
+        ("fuse", C.c_int32),
     ]
 
 
@@ -113,8 +114,8 @@ class BatchPlan(C.Structure):
         ("tile_start_offset", C.c_size_t),
         ("region_start_offset", C.c_size_t),
         ("any_split", C.c_int), ("any_noise", C.c_int),
-        ("opt_frames", C.c_int * 7), ("opt_units", C.c_int * 7),
-        ("opt_entries_offset", C.c_size_t * 7), ("opt_start_offset", C.c_size_t * 7),
+        ("opt_frames", C.c_int * 9), ("opt_units", C.c_int * 9),
+        ("opt_entries_offset", C.c_size_t * 9), ("opt_start_offset", C.c_size_t * 9),
     ]
 
 
@@ -129,7 +130,7 @@ class LaunchConfig(C.Structure):
 
 STAGE_INFO, STAGE_RECON, STAGE_EPF, STAGE_FINISH = 0, 1, 2, 3
 (STAGE_PRED, STAGE_QCO, STAGE_PATCHES, STAGE_NOISE, STAGE_GABORISH, STAGE_DOTS,
- STAGE_SPLINES) = range(4, 11)
+ STAGE_SPLINES, STAGE_FUSED, STAGE_SEAM) = range(4, 13)
 
 
 class Jpeg1Params(C.Structure):
@@ -216,6 +217,9 @@ _SIGS = {
                        C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p], C.c_int),
     "jxlr_finish": ([C.c_void_p, C.POINTER(FrameParams), C.POINTER(FrameIO), C.c_void_p,
                      C.c_size_t, C.c_void_p], C.c_int),
+    "jxlr_seam_bytes": ([C.POINTER(FrameParams)], C.c_size_t),
+    "jxlr_reconstruct_finish": ([C.c_void_p, C.POINTER(FrameParams), C.POINTER(FrameIO),
+                                 C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p], C.c_int),
     "jxlr_batch_workspace_bytes": ([C.c_int, C.POINTER(FrameParams)], C.c_size_t),
     "jxlr_batch_prepare": ([C.c_void_p, C.c_int, C.POINTER(FrameParams), C.POINTER(FrameIO),
                             C.c_void_p, C.c_size_t, C.POINTER(BatchPlan), C.c_void_p], C.c_int),
@@ -571,6 +575,21 @@ class Context:
     def finish(self, p, df, xyb, out, stream=None, noise_raw=None):
         _check(lib().jxlr_finish(self.handle, C.byref(p), C.byref(df.io(out, noise_raw=noise_raw)),
                                  xyb.data_ptr(), xyb.shape[2], _stream_handle(stream)), "finish")
+
+    def seam_buffer(self, p):
+        import torch
+        return torch.empty(max(1, lib().jxlr_seam_bytes(C.byref(p))), dtype=torch.uint8,
+                           device=f"cuda:{self.device}")
+
+    def reconstruct_finish(self, p, df, info, out, seam=None, stream=None, pred=None):
+        """The reconstruction and the finish without an XYB frame (frames with
+        no EPF pass, patches, dots, splines or noise)."""
+        if seam is None:
+            seam = self.seam_buffer(p)
+        _check(lib().jxlr_reconstruct_finish(self.handle, C.byref(p),
+                                             C.byref(df.io(out, ac_pred=pred)), info.data_ptr(),
+                                             seam.data_ptr(), seam.numel(),
+                                             _stream_handle(stream)), "reconstruct_finish")
 
     def qco_pass(self, p, df, info, xyb_orig, xyb_io, stream=None):
         _check(lib().jxlr_qco_pass(self.handle, C.byref(p), C.byref(df.io()), info.data_ptr(),

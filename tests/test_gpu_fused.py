@@ -1,0 +1,207 @@
+"""GPU tests of the reconstruction fused with the finish (frames with no EPF
+pass, patches, dots, splines or noise): jxlr_reconstruct_finish, jxlr_decode
+and the batch's FUSED and SEAM stages must equal the separate
+reconstruction and finish stages bit for bit (every pixel goes through the
+same operations in the same order), over ragged sizes (tiles cut by the
+frame edge, frames one pixel wide or high), every run length (seams between
+runs and between tile rows), every output format, Gaborish on and off, the
+split-precision transform, AC prediction and DC smoothing, and ill-formed
+regions; and the fused output against the FP64 oracle.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1908_03565_amd import workload as wl
+from tests import parity as P
+
+pytestmark = pytest.mark.gpu
+
+F32, U8, U16 = 0, 1, 2
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_1908_03565_amd import jxlr as J
+    return J.Context(0)
+
+
+def _params(f, out_format=F32, **over):
+    from paper_1908_03565_amd import jxlr as J
+    kw = dict(f["params"])
+    kw.update(epf_iters=0)
+    kw.update(over)
+    return J.params(f["xsize"], f["ysize"], out_format=out_format, **kw)
+
+
+def _staged(ctx, p, df):
+    """Reconstruction, then the finish, as separate stages."""
+    return P.gpu_stages(ctx, p, df)["out"]
+
+
+def _fused(ctx, p, df):
+    import torch
+    info = ctx.empty_info(p)
+    ctx.block_info(p, df, info)
+    pred = None
+    if p.ac_prediction:
+        pred = ctx.empty_pred(p)
+        ctx.ac_prediction(p, df, info, pred)
+    out = ctx.empty_out(p)
+    out.fill_(77)  # every pixel must be written
+    ctx.reconstruct_finish(p, df, info, out, pred=pred)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+def _decoded(ctx, p, df):
+    import torch
+    out = ctx.empty_out(p)
+    out.fill_(33)
+    ctx.decode(p, df, out, ctx.workspace(p))
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+SIZES = [(1, 1), (1, 70), (70, 1), (2, 2), (63, 31), (64, 32), (65, 33), (64, 64), (128, 32),
+         (127, 95), (200, 136), (256, 256), (300, 97), (577, 70), (640, 65)]
+
+
+@pytest.mark.parametrize("W,H", SIZES)
+@pytest.mark.parametrize("run", [1, 2, 3, 4])
+def test_fused_equals_stages_all_runs(ctx, W, H, run):
+    from paper_1908_03565_amd import jxlr as J
+    f = wl.frame(W, H, seed=7 * W + H + run, epf_iters=0)
+    df = J.DeviceFrame(f)
+    p = _params(f, fuse=run)
+    ref = _staged(ctx, _params(f, fuse=-1), df)
+    np.testing.assert_array_equal(_fused(ctx, p, df), ref)
+    np.testing.assert_array_equal(_decoded(ctx, p, df), ref)
+    assert ctx.device_status() == 0
+
+
+@pytest.mark.parametrize("fmt", [F32, U8, U16])
+@pytest.mark.parametrize("gab", [0, 1])
+def test_fused_formats_and_gaborish(ctx, fmt, gab):
+    from paper_1908_03565_amd import jxlr as J
+    f = wl.frame(333, 161, seed=500 + 10 * fmt + gab, epf_iters=0, gab=gab)
+    df = J.DeviceFrame(f)
+    ref = _staged(ctx, _params(f, fmt, fuse=-1), df)
+    for run in (0, 1, 3):
+        np.testing.assert_array_equal(_decoded(ctx, _params(f, fmt, fuse=run), df), ref,
+                                      err_msg=f"run {run}")
+
+
+@pytest.mark.parametrize("opt", ["split", "acpred", "smooth", "mixed_tiling"])
+def test_fused_options(ctx, opt):
+    from paper_1908_03565_amd import jxlr as J
+    kw, fkw = {}, {}
+    if opt == "split":
+        kw = dict(idct_split=1)
+        fkw = dict(choices=[wl.DCT8, wl.DCT16, wl.DCT32, wl.DCT16X8])
+    elif opt == "acpred":
+        kw = dict(ac_prediction=1)
+    elif opt == "smooth":
+        kw = dict(dc_smoothing=1)
+    else:
+        fkw = dict(tiling="mixed")
+    f = wl.frame(401, 229, seed=611, epf_iters=0, **fkw)
+    df = J.DeviceFrame(f)
+    ref = _staged(ctx, _params(f, fuse=-1, **kw), df)
+    for run in (1, 2, 4):
+        np.testing.assert_array_equal(_decoded(ctx, _params(f, fuse=run, **kw), df), ref,
+                                      err_msg=f"run {run}")
+
+
+def test_fused_ill_formed_region(ctx):
+    """A misaligned varblock zeroes its region in both paths and sets the
+    device flag."""
+    from paper_1908_03565_amd import jxlr as J
+    f = wl.frame(192, 96, seed=3, choices=[wl.DCT8], epf_iters=0)
+    f["strategy"][4, 5] = wl.DCT16  # misaligned, in the region at (32, 32)
+    df = J.DeviceFrame(f)
+    ref = _staged(ctx, _params(f, fuse=-1), df)
+    assert ctx.device_status() == 10
+    for run in (1, 3):
+        np.testing.assert_array_equal(_decoded(ctx, _params(f, fuse=run), df), ref)
+        assert ctx.device_status() == 10
+
+
+def test_fused_against_oracle(ctx):
+    """C1's frame (256x256, DCT8, EPF off) and a ragged mixed frame through the
+    fused decode against the FP64 oracle: max-abs 1e-4 on [0,1]-scaled RGB
+    (no integer decisions without EPF, so no pixel is excluded)."""
+    from paper_1908_03565_amd import jxlr as J
+    for f in (wl.c1(), wl.frame(203, 150, seed=9, epf_iters=0)):
+        p = _params(f)
+        out = _decoded(ctx, p, J.DeviceFrame(f))
+        q = O.params(f["xsize"], f["ysize"], **dict(f["params"], epf_iters=0))
+        ref = O.decode_stages(q, f)["rgb"]
+        err = np.abs(out.astype(np.float64) - ref).max()
+        print(f"{f['xsize']}x{f['ysize']} fused vs oracle: {err:.3g}")
+        assert err <= P.RGB_TOL
+
+
+def test_batch_fused_and_unfused_frames(ctx):
+    """A batch mixing fused frames (several sizes and formats, AC prediction)
+    with EPF frames equals each frame decoded through the stages alone; graph
+    replays too."""
+    import torch
+    from paper_1908_03565_amd import jxlr as J
+    specs = [(256, 256, 0, F32, {}), (300, 97, 0, U8, {}), (1, 70, 0, U16, {}),
+             (577, 70, 0, F32, dict(ac_prediction=1)), (200, 136, 1, U8, {}),
+             (64, 32, 0, U8, {}), (130, 66, 2, F32, {}), (640, 65, 0, U16, dict(fuse=2))]
+    ps, dfs, outs, refs = [], [], [], []
+    for i, (W, H, epf, fmt, kw) in enumerate(specs):
+        f = wl.frame(W, H, seed=900 + i, epf_iters=epf)
+        df = J.DeviceFrame(f)
+        p = _params(f, fmt, epf_iters=epf, **kw)
+        pref = _params(f, fmt, epf_iters=epf, **dict(kw, fuse=-1))
+        refs.append(_staged(ctx, pref, df))
+        ps.append(p)
+        dfs.append(df)
+        outs.append(ctx.empty_out(p))
+    ios = [df.io(o) for df, o in zip(dfs, outs)]
+    ws = ctx.batch_workspace(ps)
+    plan = ctx.batch_prepare(ps, ios, ws)
+    assert plan.opt_frames[J.STAGE_FUSED - J.STAGE_PRED] == 6
+    ctx.batch_run(plan)
+    torch.cuda.synchronize()
+    for i, (o, r) in enumerate(zip(outs, refs)):
+        np.testing.assert_array_equal(o.cpu().numpy(), r, err_msg=f"frame {i}")
+    g = ctx.graph(plan)
+    for rep in range(3):
+        for o in outs:
+            o.fill_(rep + 1)
+        torch.cuda.synchronize()
+        g.launch()
+        torch.cuda.synchronize()
+        for i, (o, r) in enumerate(zip(outs, refs)):
+            np.testing.assert_array_equal(o.cpu().numpy(), r, err_msg=f"replay {rep} frame {i}")
+    assert ctx.device_status() == 0
+
+
+def test_batch_all_fused(ctx):
+    """Every frame fused: the tile stages launch nothing, the autotuner has
+    nothing to tune, and the output equals the stages'."""
+    import torch
+    from paper_1908_03565_amd import jxlr as J
+    ps, dfs, outs, refs = [], [], [], []
+    for i in range(5):
+        f = wl.frame(96 + 64 * i, 80 + 16 * i, seed=950 + i, epf_iters=0)
+        df = J.DeviceFrame(f)
+        refs.append(_staged(ctx, _params(f, U8, fuse=-1), df))
+        p = _params(f, U8)
+        ps.append(p)
+        dfs.append(df)
+        outs.append(ctx.empty_out(p))
+    ws = ctx.batch_workspace(ps)
+    plan = ctx.batch_prepare(ps, [df.io(o) for df, o in zip(dfs, outs)], ws)
+    assert plan.total_tiles == 0
+    cfg, _ = ctx.autotune(plan, reps=1)
+    for o in outs:
+        o.fill_(5)
+    ctx.batch_run(plan, cfg)
+    torch.cuda.synchronize()
+    for i, (o, r) in enumerate(zip(outs, refs)):
+        np.testing.assert_array_equal(o.cpu().numpy(), r, err_msg=f"frame {i}")

@@ -43,7 +43,7 @@ def test_defaults_agree_with_oracle():
         # output format and transform arithmetic are the library's own; the
         # patch and dot counts travel with their arrays on the oracle's side
         if name in ("out_format", "idct_split", "num_patches", "num_dots", "num_splines",
-                    "num_spline_points"):
+                    "num_spline_points", "fuse"):
             continue
         a, b = getattr(p, name), getattr(q, name)
         if isinstance(a, C.Array):
@@ -134,21 +134,36 @@ def test_parameter_ranges():
 
 
 def test_workspace_bytes():
-    # block-info map plus one (EPF off) or two (EPF on) XYB plane sets
+    # block-info map (13 x 7 blocks, one 256-byte unit) plus, with EPF passes,
+    # two XYB plane sets; with none, the reconstruction is fused with the
+    # finish and only the seam records of the 2 x 2 tiles of 64 x 32 are kept
+    # (rows 0, 1, h - 2, h - 1 of 3 x 64 samples and columns 0, 1, w - 2,
+    # w - 1 of 3 x 32, binary32)
     p = J.params(100, 50, epf_iters=0)
-    one = J.workspace_bytes(p)
-    assert one >= 3 * 100 * 50 * 4 + 13 * 7
+    fused = J.workspace_bytes(p)
+    seam = J.lib().jxlr_seam_bytes(C.byref(p))
+    assert seam == 4 * (4 * 3 * 64 + 4 * 3 * 32) * 4
+    assert fused == 256 + seam
+    p1 = J.params(100, 50, epf_iters=1)
+    xyb = (3 * 100 * 50 * 4 + 255) // 256 * 256
+    assert J.workspace_bytes(p1) == 256 + 2 * xyb
+    assert J.lib().jxlr_seam_bytes(C.byref(p1)) == 0
     p2 = J.params(100, 50, epf_iters=2)
-    assert J.workspace_bytes(p2) - one >= 3 * 100 * 50 * 4
-    assert J.workspace_bytes(p2) % 256 == 0
+    assert J.workspace_bytes(p2) == J.workspace_bytes(p1) and J.workspace_bytes(p2) % 256 == 0
     # the quantization constraint keeps the reconstruction past a second
-    # pass: one more plane set then, none with a single pass
-    xyb = J.workspace_bytes(p2) - one
+    # pass: one more plane set then, none with a single pass or none at all
     assert J.workspace_bytes(J.params(100, 50, epf_iters=2, qco=1)) == J.workspace_bytes(p2) + xyb
     assert J.workspace_bytes(J.params(100, 50, epf_iters=1, qco=1)) == J.workspace_bytes(p2)
-    assert J.workspace_bytes(J.params(100, 50, epf_iters=0, qco=1)) == one
-    # noise adds the pseudorandom channels, one plane set
+    assert J.workspace_bytes(J.params(100, 50, epf_iters=0, qco=1)) == fused
+    # noise adds the pseudorandom channels, one plane set (and, without EPF
+    # passes, takes the unfused path: one reconstruction plane set)
     assert J.workspace_bytes(J.params(100, 50, epf_iters=2, noise=1)) - J.workspace_bytes(p2) == xyb
+    assert J.workspace_bytes(J.params(100, 50, epf_iters=0, noise=1)) == 256 + 2 * xyb
+    # fuse = -1 keeps the reconstruction and the finish apart: one plane set
+    assert J.workspace_bytes(J.params(100, 50, epf_iters=0, fuse=-1)) == 256 + xyb
+    for bad in (-2, 5):
+        assert J.workspace_bytes(J.params(100, 50, fuse=bad)) == 0
+    one = fused
     # AC prediction adds its sums, 3 x 4 floats per block (13 x 7 blocks)
     extra = J.workspace_bytes(J.params(100, 50, epf_iters=0, ac_prediction=1)) - one
     assert 12 * 4 * 13 * 7 <= extra < 12 * 4 * 13 * 7 + 256
