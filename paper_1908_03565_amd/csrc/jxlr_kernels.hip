@@ -710,10 +710,48 @@ __device__ __attribute__((always_inline)) inline void inverse_passes(
 // SPLIT: the variant with the split-precision transform (taken for the
 // regions of frames whose a.split is set); the plain variant keeps the
 // register budget of the binary32 passes alone.
+// The quantized AC of thread `tid`'s 4-sample groups of tile (tbx, tby):
+// group g = tid + 192 k is row g / 16, columns 4 (g mod 16) .. + 3 of the
+// tile, three channels.  Groups outside the coefficient planes read the
+// planes' first group and are not used.  The addresses do not depend on the
+// varblock map, so these loads are issued before anything else of the tile.
+__device__ __attribute__((always_inline)) inline void recon_load_ac(const ReconArgs& a, int tbx,
+                                                                    int tby, int tid,
+                                                                    int4 (&q)[kRecGPT][3]) {
+  const int x0 = kRecTW * tbx, y0 = kRecTH * tby;
+  const int cw = 8 * a.Wb, ch = 8 * a.Hb;
+  const bool vec = a.ac_vec;
+#pragma unroll
+  for (int k = 0; k < kRecGPT; ++k) {
+    const int g = tid + kRecThreads * k;
+    const int Y = g >> 4, X = 4 * (g & 15);
+    const bool in = g < kRecGroups && x0 + X < cw && y0 + Y < ch;
+    const size_t off = in ? size_t(y0 + Y) * a.ac_stride + x0 + X : 0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const int32_t* src = a.ac[c] + off;
+      if (vec) {
+        q[k][c] = *reinterpret_cast<const int4*>(src);
+      } else {
+        q[k][c] = make_int4(src[0], src[1], src[2], src[3]);
+      }
+    }
+  }
+}
+
+// q: the tile's AC groups (recon_load_ac), consumed by the dequantization
+// step.
 template <bool SPLIT, typename Epi>
 __device__ __attribute__((always_inline)) inline void recon_core(const ReconArgs& a, int tbx, int tby,
-                                                                 Epi&& epi) {
-  __shared__ float coef[3][kRecTH][kRecLd];
+                                                                 int4 (&q)[kRecGPT][3], Epi&& epi) {
+  // coef[c][y][x], x < 64; column kRecLd - 1 is padding that no step here
+  // reads or writes.  The array starts four floats into its storage (16-byte
+  // alignment kept), so that "column -1" of every row (the padding of the
+  // row before, or a float of the lead for the first row) is addressable
+  // with the same strides: the fused finish keeps the previous tile's last
+  // column there.
+  __shared__ __align__(16) float coef_mem[4 + 3 * kRecTH * kRecLd];
+  float (*coef)[kRecTH][kRecLd] = reinterpret_cast<float (*)[kRecTH][kRecLd]>(coef_mem + 4);
   // DC samples per tile block (b = row * 8 + column), zero-padded so that a
   // fixed 4x4 window starting at any block stays inside the array.
   __shared__ float s_dc[3][64];
@@ -735,31 +773,6 @@ __device__ __attribute__((always_inline)) inline void recon_core(const ReconArgs
   const int x0 = kRecTW * tbx, y0 = kRecTH * tby;
   const int gbx0 = x0 / 8, gby0 = y0 / 8;
   const DeviceTables* __restrict__ T = a.tab;
-
-  // The quantized AC of this thread's groups, loaded before anything else
-  // (the addresses do not depend on the varblock map).  Groups outside the
-  // coefficient planes read the planes' first group and are not used.
-  int4 q[kRecGPT][3];
-  {
-    const int cw = 8 * a.Wb, ch = 8 * a.Hb;
-    const bool vec = a.ac_vec;
-#pragma unroll
-    for (int k = 0; k < kRecGPT; ++k) {
-      const int g = tid + kRecThreads * k;
-      const int Y = g >> 4, X = 4 * (g & 15);
-      const bool in = g < kRecGroups && x0 + X < cw && y0 + Y < ch;
-      const size_t off = in ? size_t(y0 + Y) * a.ac_stride + x0 + X : 0;
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        const int32_t* src = a.ac[c] + off;
-        if (vec) {
-          q[k][c] = *reinterpret_cast<const int4*>(src);
-        } else {
-          q[k][c] = make_int4(src[0], src[1], src[2], src[3]);
-        }
-      }
-    }
-  }
 
   if (tid < 2) s_bad[tid] = 0;
   if (tid >= 64 && tid < 112) {
@@ -919,7 +932,9 @@ __device__ __attribute__((always_inline)) inline void recon_core(const ReconArgs
 // thread's 4-sample groups; an ill-formed region is written as zero.
 template <bool SPLIT>
 __device__ __attribute__((always_inline)) inline void recon_tile(const ReconArgs& a, int tbx, int tby) {
-  recon_core<SPLIT>(a, tbx, tby, [&](float (*coef)[kRecTH][kRecLd], const int* s_bad) {
+  int4 q[kRecGPT][3];
+  recon_load_ac(a, tbx, tby, threadIdx.x, q);
+  recon_core<SPLIT>(a, tbx, tby, q, [&](float (*coef)[kRecTH][kRecLd], const int* s_bad) {
     const int tid = threadIdx.x;
     const int x0 = kRecTW * tbx, y0 = kRecTH * tby;
 #pragma unroll
@@ -2209,7 +2224,7 @@ constexpr int kSeamRowF = 3 * kRecTW;
 constexpr int kSeamColF = 3 * kRecTH;
 constexpr int kSeamTileF = 4 * kSeamRowF + 4 * kSeamColF;
 constexpr int kRunMax = 4;  // tiles per run at most
-constexpr int kSeamThreads = 256;
+constexpr int kSeamThreads = kRunMax * kRecTW;  // a thread per column of a run
 // Rows of a tile per wave in the fused finish: three waves cover 32 rows.
 constexpr int kFusedRows = (kRecTH + kRecThreads / 64 - 1) / (kRecThreads / 64);
 
@@ -2222,9 +2237,10 @@ struct FusedArgs {
   int runs_x;      // runs per tile row: ceil(tiles_x / run)
 };
 
-// The finish step of tile (tx, ty), the tile's samples in coef (and the
-// last two columns of the tile before it in carry, when it is not the first
-// of its run).  first / last: the tile starts / ends its run.
+// The finish step of tile (tx, ty), the tile's samples in coef.  When the
+// tile is not the first of its run, the tile before it left its last two
+// columns in carry and its last column also in coef's column -1.  first /
+// last: the tile starts / ends its run.
 template <int FMT>
 __device__ __attribute__((always_inline)) inline void fused_tile(
     const FusedArgs& f, float (*coef)[kRecTH][kRecLd], const int* s_bad,
@@ -2247,52 +2263,28 @@ __device__ __attribute__((always_inline)) inline void fused_tile(
   }
   const bool up = ty > 0, down = ty + 1 < f.tiles_y;
   const bool left = first && tx > 0, right = last && tx + 1 < f.tiles_x;
+  const bool frame_end = tx + 1 == f.tiles_x;  // the frame's last column is in this tile
   float* rec = f.seam + (size_t(ty) * f.tiles_x + tx) * kSeamTileF;
+  // seam records: wave k copies row records k (and k + 3), lane = column;
+  // the first 128 threads copy the column records, thread = (record, row)
   if (up || down) {
-    for (int i = tid; i < 4 * kSeamRowF; i += kRecThreads) {
-      const int r = i / kSeamRowF, c = (i >> 6) % 3, x = i & 63;
+    for (int r = wave; r < 4; r += kRecThreads / 64) {
       const int y = r < 2 ? r : h - 4 + r;
-      if ((r < 2 ? up : down) && x < w && y >= 0 && y < h) rec[i] = coef[c][y][x];
+      if ((r < 2 ? up : down) && lane < w && y >= 0 && y < h) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) rec[r * kSeamRowF + c * kRecTW + lane] = coef[c][y][lane];
+      }
     }
   }
-  if (left || right) {
-    for (int i = tid; i < 4 * kSeamColF; i += kRecThreads) {
-      const int q = i / kSeamColF, c = (i >> 5) % 3, y = i & 31;
-      const int x = q < 2 ? q : w - 4 + q;
-      if ((q < 2 ? left : right) && y < h && x >= 0 && x < w)
-        rec[4 * kSeamRowF + i] = coef[c][y][x];
+  if ((left || right) && tid < 4 * kRecTH) {
+    const int q = tid >> 5, y = tid & 31;
+    const int x = q < 2 ? q : w - 4 + q;
+    if ((q < 2 ? left : right) && y < h && x >= 0 && x < w) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) rec[4 * kSeamRowF + q * kSeamColF + c * kRecTH + y] = coef[c][y][x];
     }
   }
 
-  // Lane l finishes column x0 - 1 + l: lane 0 the last column of the tile
-  // before (whose right neighbour is this tile's first column), lanes 1 ..
-  // w - 1 this tile's columns but its last, lane w its last column when the
-  // frame ends there (mirrored back into the tile).  The first column of a
-  // run with another run to its left is a seam.
-  const int gx = x0 - 1 + lane;
-  bool col;
-  if (lane == 0) col = !first;
-  else if (lane == 1 && left) col = false;
-  else if (lane < w) col = true;
-  else col = lane == w && tx + 1 == f.tiles_x;
-  // the three window columns: tile columns >= 0 from coef, -2 and -1 from
-  // carry (clamped into the arrays for lanes that store nothing)
-  const float* src[3];
-  int ld[3];
-#pragma unroll
-  for (int j = 0; j < 3; ++j) {
-    const int xj = min(max(mirror(gx - 1 + j, a.W) - x0, -2), kRecTW - 1);
-    src[j] = xj >= 0 ? &coef[0][0][xj] : &carry[0][0][xj + 2];
-    ld[j] = xj >= 0 ? kRecLd : 2;
-  }
-  auto rowidx = [&](int r) { return min(max(mirror(y0 + r, a.H) - y0, 0), h - 1); };
-  auto load_row = [&](int r, float (&wv)[3][3]) {
-    const int yy = rowidx(r);
-#pragma unroll
-    for (int c = 0; c < 3; ++c)
-#pragma unroll
-      for (int j = 0; j < 3; ++j) wv[c][j] = src[j][(c * kRecTH + yy) * ld[j]];
-  };
   T* out[3] = {static_cast<T*>(a.out[0]), static_cast<T*>(a.out[1]), static_cast<T*>(a.out[2])};
   auto finish_px = [&](int x, int r, const float (&u)[3][3], const float (&m)[3][3],
                        const float (&d)[3][3]) {
@@ -2309,47 +2301,76 @@ __device__ __attribute__((always_inline)) inline void fused_tile(
 #pragma unroll
     for (int c = 0; c < 3; ++c) out[c][o] = encode_out<FMT>(rgb[c], thr, start8);
   };
-  // rows that are seams
+  auto rowidx = [&](int r) { return min(max(mirror(y0 + r, a.H) - y0, 0), h - 1); };
   auto seam_row = [&](int r) { return (r == 0 && up) || (r == h - 1 && down); };
-  {
-    const int r0 = kFusedRows * wave, r1 = min(r0 + kFusedRows, h);
-    float wu[3][3], wm[3][3], wd[3][3];  // window rows above, at and below row r
-    load_row(r0 - 1, wu);
-    load_row(r0, wm);
-#pragma unroll 1
-    for (int r = r0; r < r1; ++r) {
-      load_row(r + 1, wd);
-      if (col && !seam_row(r)) finish_px(gx, r, wu, wm, wd);
-#pragma unroll
-      for (int c = 0; c < 3; ++c)
-#pragma unroll
-        for (int j = 0; j < 3; ++j) {
-          wu[c][j] = wm[c][j];
-          wm[c][j] = wd[c][j];
-        }
-    }
-  }
-  // the frame's last column when the tile is 64 wide (no lane 64): thread r
-  // takes row r, window columns 62, 63 and 63 mirrored
-  if (w == kRecTW && tx + 1 == f.tiles_x && tid < h && !seam_row(tid)) {
+
+  // The tile before's last column (x0 - 1): thread r takes row r, window
+  // columns from carry (the tile before's columns 62, 63) and coef's
+  // column 0.
+  if (!first && tid < h && !seam_row(tid)) {
     float wv[3][3][3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       const int yy = rowidx(tid - 1 + k);
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        wv[k][c][0] = coef[c][yy][kRecTW - 2];
-        wv[k][c][1] = coef[c][yy][kRecTW - 1];
-        wv[k][c][2] = coef[c][yy][kRecTW - 1];
+        wv[k][c][0] = carry[c][yy][0];
+        wv[k][c][1] = carry[c][yy][1];
+        wv[k][c][2] = coef[c][yy][0];
       }
     }
-    finish_px(x0 + kRecTW - 1, tid, wv[0], wv[1], wv[2]);
+    finish_px(x0 - 1, tid, wv[0], wv[1], wv[2]);
   }
+
+  // Lane l takes column x0 + l of rows kFusedRows * wave ..: every column
+  // but the last one, which the next tile of the run takes (or the seam pass
+  // at the end of a run), unless the frame ends there; column 0 of a run
+  // with another run to its left is a seam.  Window columns l - 1, l, l + 1
+  // (mirrored at the frame's edges; -1: the tile before's last column, kept
+  // in coef's column -1), read at uniform strides.
+  {
+    const bool col = (lane == 0 && left) ? false : lane < w - 1 ? true : (lane == w - 1 && frame_end);
+    const int cm = x0 + lane == 0 ? 0 : lane - 1;
+    const int cp = x0 + lane + 1 == a.W ? lane : lane + 1;
+    const float* base = &coef[0][0][0];
+    const int r0 = kFusedRows * wave, r1 = min(r0 + kFusedRows, h);
+    auto load_row = [&](int r, float (&wv)[3][3]) {
+      const float* rp = base + rowidx(r) * kRecLd;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        wv[c][0] = rp[c * kRecTH * kRecLd + cm];
+        wv[c][1] = rp[c * kRecTH * kRecLd + lane];
+        wv[c][2] = rp[c * kRecTH * kRecLd + cp];
+      }
+    };
+    // rolling window rows, three steps per iteration so that the rows
+    // change roles without register moves
+    float wa[3][3], wb[3][3], wc[3][3];
+    load_row(r0 - 1, wa);
+    load_row(r0, wb);
+#pragma unroll 1
+    for (int r = r0; r < r1; r += 3) {
+      load_row(r + 1, wc);
+      if (col && !seam_row(r)) finish_px(x0 + lane, r, wa, wb, wc);
+      if (r + 1 >= r1) break;
+      load_row(r + 2, wa);
+      if (col && !seam_row(r + 1)) finish_px(x0 + lane, r + 1, wb, wc, wa);
+      if (r + 2 >= r1) break;
+      load_row(r + 3, wb);
+      if (col && !seam_row(r + 2)) finish_px(x0 + lane, r + 2, wc, wa, wb);
+    }
+  }
+
   if (!last) {
-    __syncthreads();  // every read of carry for this tile is done
-    for (int i = tid; i < 3 * kRecTH * 2; i += kRecThreads) {
-      const int k = i & 1, y = (i >> 1) & 31, c = i >> 6;
-      carry[c][y][k] = coef[c][y][kRecTW - 2 + k];
+    __syncthreads();  // every read of carry and of column -1 for this tile is done
+    // columns 62 and 63 into carry, column 63 also into column -1 (the
+    // padding of the row before: no step of recon_core touches it)
+    if (tid < 3 * kRecTH) {
+      const int c = tid >> 5, y = tid & 31;
+      const float v62 = coef[c][y][kRecTW - 2], v63 = coef[c][y][kRecTW - 1];
+      carry[c][y][0] = v62;
+      carry[c][y][1] = v63;
+      coef[c][y][-1] = v63;
     }
   }
 }
@@ -2374,7 +2395,11 @@ __device__ __attribute__((always_inline)) inline void fused_unit(const FusedArgs
   const int tx1 = min(tx0 + f.run, f.tiles_x);
   for (int tx = tx0; tx < tx1; ++tx) {
     if (tx > tx0) __syncthreads();  // the previous tile's reads of LDS are done
-    recon_core<SPLIT>(f.rec, tx, ty, [&](float (*coef)[kRecTH][kRecLd], const int* s_bad) {
+    int tid = threadIdx.x;  // opaque, as in recon_core
+    asm volatile("" : "+v"(tid));
+    int4 q[kRecGPT][3];
+    recon_load_ac(f.rec, tx, ty, tid, q);
+    recon_core<SPLIT>(f.rec, tx, ty, q, [&](float (*coef)[kRecTH][kRecLd], const int* s_bad) {
       const bool first = tx == tx0, last = tx + 1 == tx1;
       if (fmt == JXLR_OUT_F32)
         fused_tile<JXLR_OUT_F32>(f, coef, s_bad, carry, tx, ty, first, last, nullptr, nullptr);
@@ -2387,71 +2412,105 @@ __device__ __attribute__((always_inline)) inline void fused_unit(const FusedArgs
   }
 }
 
-// Sample (channel c, column gx, row gy) from the seam records; the position
-// is one that some seam pixel's window needs (see fused_tile).
-__device__ inline float seam_sample(const FusedArgs& f, int c, int gx, int gy) {
-  const int tx = gx / kRecTW, ty = gy / kRecTH, lx = gx - kRecTW * tx, ly = gy - kRecTH * ty;
-  const int w = min(kRecTW, f.fin.W - kRecTW * tx), h = min(kRecTH, f.fin.H - kRecTH * ty);
-  const float* rec = f.seam + (size_t(ty) * f.tiles_x + tx) * kSeamTileF;
-  if (ly <= 1 && ty > 0) return rec[ly * kSeamRowF + c * kRecTW + lx];
-  if (ly >= h - 2 && ty + 1 < f.tiles_y) return rec[(ly - h + 4) * kSeamRowF + c * kRecTW + lx];
-  if (lx <= 1) return rec[4 * kSeamRowF + lx * kSeamColF + c * kRecTH + ly];
-  return rec[4 * kSeamRowF + (lx - w + 4) * kSeamColF + c * kRecTH + ly];
-}
-
-// The seam pixels of run u: its top and bottom rows where another tile row
-// is there, and its first / last column (rows between those) where another
-// run is there.
+// The seam pass, one workgroup per run (tile row ty, run tr of it): the
+// horizontal seam along the run's top edge (the last row of the tile row
+// above and the first row of this one, over the run's columns) when there
+// is a tile row above, and the vertical seam along its left edge (the last
+// column of the run to the left and the first of this one, over the rows
+// that are not in a horizontal seam) when there is a run to the left.
+// Thread j takes column X0 + j of the horizontal seam (both its pixels)
+// and row j of the vertical one (both its pixels), reading its windows
+// straight from the seam records (neighbouring threads read neighbouring
+// samples, so the reads coalesce).
 template <int FMT>
 __device__ inline void seam_pixels(const FusedArgs& f, int u, const float* __restrict__ thr,
                                    const uint8_t* __restrict__ start8) {
   using T = typename OutT<FMT>::T;
   const FinishArgs& a = f.fin;
+  const int tid = threadIdx.x;
   const int ty = u / f.runs_x, tr = u - ty * f.runs_x;
   const int X0 = kRecTW * f.run * tr, X1 = min(X0 + kRecTW * f.run, a.W);
   const int y0 = kRecTH * ty, h = min(kRecTH, a.H - y0);
-  const bool up = ty > 0, down = ty + 1 < f.tiles_y;
-  const int ntop = up ? X1 - X0 : 0, nbot = down ? X1 - X0 : 0;
-  const int ya = up ? 1 : 0, yb = down ? h - 1 : h;
-  const int ncol = max(yb - ya, 0);
-  const int nl = X0 > 0 ? ncol : 0, nr = X1 < a.W ? ncol : 0;
-  const int total = ntop + nbot + nl + nr;
-  for (int i = threadIdx.x; i < total; i += kSeamThreads) {
-    int gx, gy;
-    if (i < ntop) {
-      gx = X0 + i;
-      gy = y0;
-    } else if (i < ntop + nbot) {
-      gx = X0 + (i - ntop);
-      gy = y0 + h - 1;
-    } else if (i < ntop + nbot + nl) {
-      gx = X0;
-      gy = y0 + ya + (i - ntop - nbot);
-    } else {
-      gx = X1 - 1;
-      gy = y0 + ya + (i - ntop - nbot - nl);
-    }
-    const int xs[3] = {mirror(gx - 1, a.W), gx, mirror(gx + 1, a.W)};
-    const int ys[3] = {mirror(gy - 1, a.H), gy, mirror(gy + 1, a.H)};
-    float wv[3][3][3];
-#pragma unroll
-    for (int k = 0; k < 3; ++k)
-#pragma unroll
-      for (int c = 0; c < 3; ++c)
-#pragma unroll
-        for (int j = 0; j < 3; ++j) wv[k][c][j] = seam_sample(f, c, xs[j], ys[k]);
+  const bool hseam = ty > 0, vseam = X0 > 0;
+  const float* seam = f.seam;
+  const size_t trow = size_t(f.tiles_x) * kSeamTileF;  // one tile row of records
+  auto finish_px = [&](int gx, int gy, const float (&wu)[3][3], const float (&wm)[3][3],
+                       const float (&wd)[3][3]) {
     float v[3];
     if (a.gab) {
-      gab_pixel(a, wv[0], wv[1], wv[2], v);
+      gab_pixel(a, wu, wm, wd, v);
     } else {
 #pragma unroll
-      for (int c = 0; c < 3; ++c) v[c] = wv[1][c][1];
+      for (int c = 0; c < 3; ++c) v[c] = wm[c][1];
     }
     float rgb[3];
     xyb_to_rgb(a, v, rgb);
     const size_t o = size_t(gy) * a.out_stride + gx;
 #pragma unroll
     for (int c = 0; c < 3; ++c) static_cast<T*>(a.out[c])[o] = encode_out<FMT>(rgb[c], thr, start8);
+  };
+  if (hseam && tid < X1 - X0) {
+    // rows y0 - 2, y0 - 1 (records 2, 3 of the tile row above, which is 32
+    // rows high) and y0, y0 + 1 (records 0, 1 of this one; row 0 again
+    // when it is one row high), columns x - 1, x, x + 1 mirrored
+    const int x = X0 + tid;
+    const float* p[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const int gx = mirror(x - 1 + d, a.W), tx = gx / kRecTW;
+      p[d] = seam + size_t(ty) * trow + size_t(tx) * kSeamTileF + (gx - kRecTW * tx);
+    }
+    const int r3 = h == 1 ? 0 : kSeamRowF;
+    float w[4][3][3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const float* pu = p[d] - trow;  // the same column's tile in the row above
+        w[0][c][d] = pu[2 * kSeamRowF + c * kRecTW];
+        w[1][c][d] = pu[3 * kSeamRowF + c * kRecTW];
+        w[2][c][d] = p[d][c * kRecTW];
+        w[3][c][d] = p[d][r3 + c * kRecTW];
+      }
+    finish_px(x, y0 - 1, w[0], w[1], w[2]);
+    finish_px(x, y0, w[1], w[2], w[3]);
+  }
+  if (vseam) {
+    // columns X0 - 2, X0 - 1 (records 2, 3 of the tile to the left, which
+    // is 64 columns wide) and X0, X0 + 1 (records 0, 1 of this tile; column
+    // 0 again when it is one column wide), rows mirrored inside the tile row
+    const int ya = hseam ? 1 : 0, yb = ty + 1 < f.tiles_y ? h - 1 : h;
+    const int y = ya + tid;
+    if (y < yb) {
+      const int tx = X0 / kRecTW, w1 = min(kRecTW, a.W - X0) == 1 ? 0 : kSeamColF;
+      const float* lf = seam + size_t(ty) * trow + size_t(tx - 1) * kSeamTileF + 4 * kSeamRowF;
+      const float* rt = lf + kSeamTileF;
+      float w[3][4][3];  // [window row][column X0 - 2 ..][channel]
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const int yy = mirror(y0 + y - 1 + k, a.H) - y0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          w[k][0][c] = lf[2 * kSeamColF + c * kRecTH + yy];
+          w[k][1][c] = lf[3 * kSeamColF + c * kRecTH + yy];
+          w[k][2][c] = rt[c * kRecTH + yy];
+          w[k][3][c] = rt[w1 + c * kRecTH + yy];
+        }
+      }
+#pragma unroll
+      for (int q0 = 0; q0 < 2; ++q0) {
+        float wu[3][3], wm[3][3], wd[3][3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+          for (int d = 0; d < 3; ++d) {
+            wu[c][d] = w[0][q0 + d][c];
+            wm[c][d] = w[1][q0 + d][c];
+            wd[c][d] = w[2][q0 + d][c];
+          }
+        finish_px(X0 - 1 + q0, y0 + y, wu, wm, wd);
+      }
+    }
   }
 }
 
