@@ -809,7 +809,7 @@ def main():
     ap.add_argument("--splines", type=int, default=0, metavar="N",
                     help="single-frame workloads: N synthetic splines (K.4)")
     ap.add_argument("--split", action="store_true",
-                    help="split-precision (bf16 hi+lo matrix-core) inverse transform")
+                    help="split-precision (block-scaled f16 hi+lo matrix-core) inverse transform")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB a few times (the reference "
                          "kernel that scales the HBM byte counters) and exit")

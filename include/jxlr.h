@@ -131,10 +131,12 @@ typedef struct {
   int32_t  out_format;         /* jxlr_out_format */
   /* Inverse-transform arithmetic.  0: binary32 throughout (the plain form).
    * 1: split precision, for every 32x32 region tiled by varblocks of one
-   * DCT type (DCT8, DCT16, DCT32 and the rectangular DCTs): each pass is a
-   * matrix product on the matrix cores with operands split into bfloat16
-   * high and low parts, hi*hi + hi*lo + lo*hi accumulated in binary32; other
-   * regions use the plain form. */
+   * DCT type (DCT8, DCT16, DCT32 and the rectangular DCTs): the column and
+   * the row pass of the high-frequency coefficients are matrix products on
+   * the matrix cores, their operands scaled by a power of two per wave and
+   * split into binary16 high and low parts, hi*hi + hi*lo + lo*hi
+   * accumulated in binary32; each varblock's LLF corner is transformed in
+   * binary32 beside them; other regions use the plain form. */
   int32_t  idct_split;
   /* Adaptive DC smoothing of F.2 (1) or not (0, the default; the draft's
    * kSkipAdaptiveDCSmoothing case): each dequantized DC sample away from the

@@ -492,11 +492,6 @@ void srgb_thresholds(int bits, float* thr) {
   }
 }
 
-uint16_t bf16_rne(float v) {
-  uint32_t u;
-  std::memcpy(&u, &v, 4);
-  return uint16_t((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
-}
 
 uint16_t f16_rne(double v) {
   // sign, then the magnitude as an integer count of the format's spacing at
@@ -524,13 +519,6 @@ double f16_value(uint16_t h) {
 }
 
 namespace {
-float bf16_value(uint16_t h) {
-  const uint32_t u = uint32_t(h) << 16;
-  float v;
-  std::memcpy(&v, &u, 4);
-  return v;
-}
-
 void build_mfma_operands(DeviceTables* t) {
   const double pi = 3.14159265358979323846;
   for (int m = 0; m < 3; ++m) {
@@ -540,10 +528,6 @@ void build_mfma_operands(DeviceTables* t) {
         for (int e = 0; e < 8; ++e) {
           const int i = l % 32, k = 16 * step + 8 * (l / 32) + e;
           const double a = i / N == k / N ? std::cos(pi * (2 * (i % N) + 1) * (k % N) / (2.0 * N)) : 0.0;
-          const uint16_t hi = bf16_rne(float(a));
-          const uint16_t lo = bf16_rne(float(a - double(bf16_value(hi))));
-          t->mfma_a[m][0][step][l][e] = hi;
-          t->mfma_a[m][1][step][l][e] = lo;
           const uint16_t hh = f16_rne(16.0 * a);
           t->mfma_h[m][0][step][l][e] = hh;
           t->mfma_h[m][1][step][l][e] = f16_rne(16.0 * a - f16_value(hh));

@@ -75,14 +75,12 @@ struct DeviceTables {
   // Split-precision transform operands: the plain DCT-III matrix of a
   // 32-sample region side made of 32 / N diagonal N-point blocks (m = 0, 1, 2
   // for N = 8, 16, 32), A[i][k] = cos(pi (2 (i mod N) + 1)(k mod N) / (2 N))
-  // when i / N == k / N, else 0, as bfloat16 bit patterns of its high part
-  // (part 0, A rounded to nearest even) and of the rest (part 1), in the
+  // when i / N == k / N, else 0, times 16 (so that the rests of the smallest
+  // cosines stay normal numbers), as binary16 bit patterns of its high part
+  // (part 0, rounded to nearest even) and of the rest (part 1), in the
   // A-operand order of a 32x32x16 matrix instruction: element e of lane l in
-  // k-step t is A[l mod 32][16 t + 8 (l / 32) + e].
-  alignas(16) uint16_t mfma_a[3][2][2][64][8];
-  // The same matrices times 16, as binary16 high parts (part 0, rounded to
-  // nearest even) and rests (part 1): the split form's A operands (times 16
-  // so that the rests of the smallest cosines stay normal numbers).
+  // k-step t is A[l mod 32][16 t + 8 (l / 32) + e].  The split form's A
+  // operands.
   alignas(16) uint16_t mfma_h[3][2][2][64][8];
   // The same cosines in binary32 for the varblocks' LLF corners, which the
   // split form transforms outside the matrix products: llf_cos[m][n][u] =
@@ -160,8 +158,6 @@ int srgb_code_f64(int bits, float v);
 void srgb_thresholds(int bits, float* thr);
 // Fills DeviceTables::srgb_start8; false if a bucket spans more than two codes.
 bool srgb_bucket_starts(uint8_t* start);
-// bfloat16 bit pattern of v rounded to nearest, ties to even.
-uint16_t bf16_rne(float v);
 // binary16 bit pattern of v rounded to nearest, ties to even (finite v
 // within the binary16 range), and its value.
 uint16_t f16_rne(double v);

@@ -28,7 +28,7 @@ const float* shim_a16s() { return g_tables.a16s; }
 const float* shim_a32s() { return g_tables.a32s; }
 const int32_t* shim_mul(int shift) { return g_tables.mul_table[shift]; }
 int shim_dq_offset(int s) { return jxlr::dq_offset(s); }
-const uint16_t* shim_mfma(int m) { return &g_tables.mfma_a[m][0][0][0][0]; }
+const uint16_t* shim_mfma(int m) { return &g_tables.mfma_h[m][0][0][0][0]; }
 const float* shim_thr(int bits) { return bits == 8 ? g_tables.srgb_thr8 : g_tables.srgb_thr16; }
 const uint8_t* shim_start8() { return g_tables.srgb_start8; }
 int shim_bucket0() { return jxlr::kSrgbBucket0; }

@@ -87,7 +87,10 @@ def test_batch_any_grid(ctx, grids):
     ws = ctx.batch_workspace(ps)
     plan = ctx.batch_prepare(ps, ios, ws)
     assert plan.n == len(ps)
-    assert plan.total_tiles == sum(((p.xsize + 63) // 64) * ((p.ysize + 31) // 32) for p in ps)
+    # the tile stages take the frames with EPF passes; the others are fused
+    assert plan.total_tiles == sum(((p.xsize + 63) // 64) * ((p.ysize + 31) // 32) for p in ps
+                                   if p.epf_iters > 0)
+    assert plan.opt_frames[J.STAGE_FUSED - J.STAGE_PRED] == sum(p.epf_iters == 0 for p in ps)
     assert plan.max_epf_iters == 3
     _fill(outs)
     ctx.batch_run(plan, J.LaunchConfig(*grids))
@@ -222,6 +225,8 @@ def test_autotune_and_stages(ctx, tmp_path):
     assert info2["cached"] and cfg2.as_dict() == cfg.as_dict()
     _fill(outs)
     ctx.batch_stage(plan, J.STAGE_INFO, 0, 0, 0)
+    ctx.batch_stage(plan, J.STAGE_FUSED, 0, 0, 0)
+    ctx.batch_stage(plan, J.STAGE_SEAM, 0, 0, 0)
     ctx.batch_stage(plan, J.STAGE_RECON, cfg.grid_recon, cfg.order_recon, 0)
     for k in range(plan.max_epf_iters):
         ctx.batch_stage(plan, J.STAGE_EPF, cfg.grid_epf, cfg.order_epf, k)

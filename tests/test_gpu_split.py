@@ -1,6 +1,8 @@
 """GPU parity of the split-precision inverse transform (idct_split = 1): the
-column and row products of every 32x32 region tiled by one DCT type run on
-the matrix cores with bfloat16 hi/lo operands and binary32 accumulation.
+column and row products of the high-frequency coefficients of every 32x32
+region tiled by one DCT type run on the matrix cores with block-scaled
+binary16 hi/lo operands and binary32 accumulation (the LLF corners stay in
+binary32).
 
 Gate: max-abs 1e-3 on [0,1]-scaled linear RGB against the FP64 oracle
 (outside EPF flip-affected pixels, as for the plain form).  The XYB
@@ -48,6 +50,13 @@ def test_split_reconstruction_per_type(ctx, s):
     # 128x96: every region is whole and uniform, so all of it takes the
     # matrix-core path
     f = wl.frame(128, 96, seed=80 + s, choices=[s], epf_iters=1)
+    if s in (wl.DCT32X8, wl.DCT8X32):
+        # the default DCT32X8 / DCT8X32 B-channel weights turn this recipe's
+        # coefficients into samples hundreds of times the XYB range (RGB
+        # grows with their cube): for an absolute RGB gate, the B channel's
+        # AC is dropped and the quant field raised to 256 (AcMul 1/32)
+        f["ac"][2] = 0
+        f["qf"][:] = 255
     p, gs = _stages(ctx, f, 1)
     _, gp = _stages(ctx, f, 0)
     orc = _oracle(f)
@@ -58,16 +67,9 @@ def test_split_reconstruction_per_type(ctx, s):
     assert np.all(err <= SPLIT_XYB_REL * np.maximum(scale, 1.0))
     assert not np.array_equal(gs["recon"], gp["recon"])  # the other path did run
     cmp = P.compare_rgb(p, gs, orc)
-    print(f"type {s}: split RGB {cmp}")
-    if s in (wl.DCT32X8, wl.DCT8X32):
-        # the default DCT32X8 / DCT8X32 B-channel weights turn this recipe's
-        # coefficients into samples hundreds of times the XYB range (RGB grows
-        # with the cube of XYB), where an absolute RGB gate says nothing: these
-        # two are held to the relative XYB bound above
-        assert cmp["max_abs_ref"] > 64.0
-    else:
-        assert cmp["max_abs_ref"] <= 64.0
-        assert cmp["max_err"] <= SPLIT_TOL
+    print(f"type {s}: split RGB {({k: v for k, v in cmp.items() if k != 'mask'})}")
+    assert cmp["max_abs_ref"] <= 64.0
+    assert cmp["max_err"] <= SPLIT_TOL
 
 
 @pytest.mark.parametrize("s", [wl.DCT2, wl.DCT4, wl.IDENTITY])
@@ -95,13 +97,18 @@ def test_split_mixed_and_ragged(ctx):
 
 def test_c3_full_size_split_and_plain(ctx):
     """4096x4096, half of the regions DCT32: both forms against the oracle,
-    with the max-abs error per transform type.  The split form's sample errors
-    (about 1e-5 of the sample scale) cross EPF guide-byte boundaries far more
-    often than binary32's, and each crossing marks a 11x9 footprint for two
-    passes, so its flip-affected share is larger."""
+    with the max-abs error per transform type, over every pixel outside the
+    flip-affected ones and with the affected share bounded.  Measured: plain
+    2.2e-5 with 32,308 affected pixels (0.19%), split 2.0e-5 with 32,541
+    (0.19%): with the high-frequency part alone on the matrix cores and
+    block-scaled binary16 operands, the split form's samples cross EPF guide
+    boundaries about as often as binary32's.  Bounds: 0.5% of the pixels for
+    each form (2.5x the measured share) and the split form's share at most
+    1.5x the plain one's."""
     f = wl.c3()
     orc = _oracle(f)
-    for split, tol, share in ((0, P.RGB_TOL, 0.05), (1, SPLIT_TOL, 0.25)):
+    affected = {}
+    for split, tol in ((0, P.RGB_TOL), (1, SPLIT_TOL)):
         p, g = _stages(ctx, f, split)
         cmp = P.compare_rgb(p, g, orc)
         per = P.max_err_by_type(f, g, orc, cmp["mask"])
@@ -109,4 +116,6 @@ def test_c3_full_size_split_and_plain(ctx):
               f"flips {cmp['passes']}); per type {per}")
         assert cmp["max_err"] <= tol
         assert max(per.values()) <= tol
-        assert cmp["affected"] <= share * cmp["pixels"]
+        assert cmp["affected"] <= 0.005 * cmp["pixels"]
+        affected[split] = cmp["affected"]
+    assert affected[1] <= 1.5 * affected[0]

@@ -517,11 +517,12 @@ def test_srgb_8bit_bucket_code_is_oracle_rounding(shim):
 
 @pytest.mark.parametrize("m", [0, 1, 2])
 def test_split_transform_operands(shim, m):
-    # the split matrices, put back in matrix order, are the block-diagonal
-    # plain DCT-III of 8 << m points; hi is the bfloat16 rounding of each
-    # entry and hi + lo is within 2^-17 of it
+    # the split matrices, put back in matrix order, are 16 times the
+    # block-diagonal plain DCT-III of 8 << m points; hi is the binary16
+    # rounding of each entry and hi + lo is within 2^-21 of it (in units of
+    # the unscaled matrix)
     raw = np.ctypeslib.as_array(shim.shim_mfma(m), shape=(2 * 2 * 64 * 8,)).copy()
-    parts = (raw.astype(np.uint32) << 16).view(np.float32).reshape(2, 2, 64, 8).astype(np.float64)
+    parts = raw.view(np.float16).reshape(2, 2, 64, 8).astype(np.float64) / 16.0
     A = np.zeros((2, 32, 32))
     for part in range(2):
         for step in range(2):
@@ -531,10 +532,9 @@ def test_split_transform_operands(shim, m):
     N = 8 << m
     i, k = np.meshgrid(np.arange(32), np.arange(32), indexing="ij")
     ref = np.where(i // N == k // N, np.cos(np.pi * (2 * (i % N) + 1) * (k % N) / (2 * N)), 0.0)
-    assert np.abs(A[0] + A[1] - ref).max() <= 2.0 ** -17
-    hi_bits = raw.reshape(2, 2, 64, 8)[0]
-    assert np.all(np.abs(A[0] - ref) <= np.abs(ref) * 2.0 ** -8 + 1e-30)
-    assert hi_bits.dtype == np.uint16
+    assert np.abs(A[0] + A[1] - ref).max() <= 2.0 ** -21
+    assert np.all(np.abs(A[0] - ref) <= np.abs(ref) * 2.0 ** -11 + 1e-30)
+    assert np.array_equal(np.float16(16.0 * ref).astype(np.float64) / 16.0, A[0])
 
 
 def test_crops_are_well_formed_frames():
