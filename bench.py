@@ -458,12 +458,20 @@ def bench_batch(args, J, wl, torch, np):
     n_epf = plan.max_epf_iters
     fused_px = sum(p.xsize * p.ysize for p in ps if p.fuse >= 0 and p.epf_iters == 0)
     tile_px = px - fused_px
+    # frames finished in their last EPF pass (nothing between it and the
+    # finish) and frames whose reconstruction is fused with the finish
+    fin_fused = lambda p: p.fuse >= 0 and not (p.qco and p.epf_iters) and not p.noise and \
+        not (p.num_patches or p.num_dots or p.num_splines)
+    epf_fin_px = sum(p.xsize * p.ysize for p in ps if fin_fused(p) and p.epf_iters > 0)
     stages = [("info", J.STAGE_INFO, cfg.grid_info, 0, 0)]
     if fused_px:
-        stages += [("fused", J.STAGE_FUSED, 0, 0, 0), ("seam", J.STAGE_SEAM, 0, 0, 0)]
+        stages.append(("fused", J.STAGE_FUSED, 0, 0, 0))
     if tile_px:
         stages.append(("reconstruct", J.STAGE_RECON, cfg.grid_recon, cfg.order_recon, 0))
         stages += [(f"epf{k}", J.STAGE_EPF, cfg.grid_epf, cfg.order_epf, k) for k in range(n_epf)]
+    if fused_px or epf_fin_px:
+        stages.append(("seam", J.STAGE_SEAM, 0, 0, 0))
+    if tile_px > epf_fin_px:
         stages.append(("finish", J.STAGE_FINISH, cfg.grid_finish, cfg.order_finish, 0))
     reps = max(3, args.steps // 2)
     sev = [[torch.cuda.Event(enable_timing=True) for _ in range(len(stages) + 1)]
@@ -483,10 +491,18 @@ def bench_batch(args, J, wl, torch, np):
     log(f"bench: eager stages {({k: round(v, 4) for k, v in sms.items()})} (sum {eager_ms:.4f} ms)")
     fmt = ps[0].out_format
     kernels = {}
-    if tile_px:
-        kernels = kernel_table(tile_px, recon_ms, statistics.mean(epf_ms) if n_epf else None,
-                               fin_ms, fmt,
-                               ("recon_batch_kernel", "epf_batch_kernel", "finish_batch_kernel"))
+    if recon_ms is not None:
+        kernels["recon_batch_kernel"] = dict(
+            ms=recon_ms, bound="hbm", bytes_per_px=RECON_BYTES_PER_PX,
+            achieved=tile_px * RECON_BYTES_PER_PX / (recon_ms / 1e3) / 1e9)
+    if epf_ms:
+        m = statistics.mean(epf_ms)
+        kernels["epf_batch_kernel"] = dict(ms=m, bound="alu",
+                                           achieved=tile_px * EPF_OPS_PER_PX / (m / 1e3) / 1e12)
+    if fin_ms is not None:
+        kernels["finish_batch_kernel"] = dict(
+            ms=fin_ms, bound="hbm", bytes_per_px=FINISH_BYTES_PER_PX[fmt],
+            achieved=(tile_px - epf_fin_px) * FINISH_BYTES_PER_PX[fmt] / (fin_ms / 1e3) / 1e9)
     if fused_px:
         fb = FUSED_BYTES_PER_PX[fmt]
         kernels["fused_batch_kernel"] = dict(
@@ -576,7 +592,9 @@ def bench_batch(args, J, wl, torch, np):
         "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 5),
                        "p99": round(float(np.percentile(lat, 99)), 5)},
         "stage_ms": {**{k: round(v, 5) for k, v in sms.items() if not k.startswith("epf")},
-                     "epf": [round(x, 5) for x in epf_ms], "eager_sum": round(eager_ms, 5)},
+                     "epf": [round(x, 5) for x in epf_ms], "eager_sum": round(eager_ms, 5),
+                     **({"finish_in_last_epf_pass_mp": round(epf_fin_px / 1e6, 4)}
+                        if epf_fin_px else {})},
         "host_wall_ms_per_step": round(wall / args.steps * 1e3, 5),
         "error": err,
         "end_to_end_hbm": e2e,

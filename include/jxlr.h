@@ -440,6 +440,24 @@ jxlr_status jxlr_noise_channels(jxlr_ctx* ctx, const jxlr_frame_params* p, float
 jxlr_status jxlr_finish(jxlr_ctx* ctx, const jxlr_frame_params* p, const jxlr_frame_io* io,
                         const float* xyb, size_t xyb_stride, hipStream_t stream);
 
+/* The last edge-preserving filter pass (as jxlr_epf_pass from xyb_in)
+ * followed by the finish (as jxlr_finish) without storing the pass's
+ * output, for a frame with EPF passes and nothing between the last one and
+ * the finish: no quantization constraint (J.3) and no patches, dots,
+ * splines or noise (Annex K).  Output into io->out in p->out_format, equal
+ * bit for bit to jxlr_epf_pass then jxlr_finish.  Each workgroup filters a
+ * 64x32 tile, keeps the result on chip and finishes the pixels whose
+ * Gaborish window lies in the tile; the samples along tile boundaries go to
+ * `seam` (device memory owned by the caller, at least jxlr_seam_bytes(p)
+ * bytes, overwritten) and a second launch on the same stream finishes the
+ * boundary pixels.  Errors: JXLR_E_PARAM for a frame that does not qualify,
+ * JXLR_E_WORKSPACE for a seam buffer below jxlr_seam_bytes(p), and those of
+ * jxlr_epf_pass and jxlr_finish.  jxlr_decode takes this path for the last
+ * pass of every frame that qualifies. */
+jxlr_status jxlr_epf_finish(jxlr_ctx* ctx, const jxlr_frame_params* p, const jxlr_frame_io* io,
+                            const uint8_t* info, const float* xyb_in, size_t xyb_stride,
+                            float* seam, size_t seam_bytes, hipStream_t stream);
+
 /* The reconstruction (as jxlr_reconstruct) followed by the finish (as
  * jxlr_finish) without an intermediate XYB frame, for a frame whose
  * reconstruction goes to the finish unchanged: no EPF pass (C.10) and no
@@ -454,7 +472,8 @@ jxlr_status jxlr_finish(jxlr_ctx* ctx, const jxlr_frame_params* p, const jxlr_fr
  * JXLR_E_WORKSPACE for a seam buffer below jxlr_seam_bytes(p), and those of
  * jxlr_reconstruct and jxlr_finish.  jxlr_decode takes this path for every
  * frame that qualifies. */
-size_t jxlr_seam_bytes(const jxlr_frame_params* p); /* 0 if the frame does not qualify */
+/* 0 for a frame that qualifies for neither fused path */
+size_t jxlr_seam_bytes(const jxlr_frame_params* p);
 jxlr_status jxlr_reconstruct_finish(jxlr_ctx* ctx, const jxlr_frame_params* p,
                                     const jxlr_frame_io* io, const uint8_t* info, float* seam,
                                     size_t seam_bytes, hipStream_t stream);
@@ -545,15 +564,16 @@ jxlr_status jxlr_jpeg1_decode(jxlr_ctx* ctx, const jxlr_jpeg1_params* p,
  * stages: one launch each over the frames that use it.  Results are
  * bit-identical to jxlr_decode of each frame alone. */
 
-/* Stages of a batch, for jxlr_batch_stage.  The tile stages INFO, RECON, EPF
- * and FINISH take every frame (INFO) or every frame outside FUSED (the
- * others); the option stages PRED (Annex H, before RECON), QCO (J.3, after
- * the EPF passes), PATCHES (K.3), NOISE (K.5 channels), GABORISH (J.4 as
- * its own pass, for frames with dots or splines), DOTS (K.2) and SPLINES
- * (K.4), in this order before FINISH, take the frames that use them; FUSED
- * and SEAM (after PRED) take the frames jxlr_reconstruct_finish qualifies
- * (no EPF pass, patches, dots, splines or noise) and do for them what
- * jxlr_reconstruct_finish does, reconstruction to output. */
+/* Stages of a batch, for jxlr_batch_stage, in the order jxlr_batch_run
+ * runs them: INFO (every frame); PRED (Annex H); FUSED (the frames
+ * jxlr_reconstruct_finish qualifies: reconstruction to output); the tile
+ * stages RECON and EPF (every other frame; a frame with fewer passes sits
+ * out the later ones, and the last pass of a frame jxlr_epf_finish
+ * qualifies also finishes it); SEAM (the boundary pixels of both fused
+ * kinds); QCO (J.3), PATCHES (K.3), NOISE (K.5 channels), GABORISH (J.4 as
+ * its own pass, for frames with dots or splines), DOTS (K.2), SPLINES (K.4);
+ * FINISH (the frames not finished by then).  Each option stage takes the
+ * frames that use it. */
 enum {
   JXLR_STAGE_INFO = 0, JXLR_STAGE_RECON = 1, JXLR_STAGE_EPF = 2, JXLR_STAGE_FINISH = 3,
   JXLR_STAGE_PRED = 4, JXLR_STAGE_QCO = 5, JXLR_STAGE_PATCHES = 6, JXLR_STAGE_NOISE = 7,

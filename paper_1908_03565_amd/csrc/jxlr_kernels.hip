@@ -1683,9 +1683,15 @@ __device__ inline uint32_t guide_byte(float v, float minv, float scale) {
   return uint32_t(g);  // truncation is the floor on [0, 255]
 }
 
-// One 64x32 output tile of an EPF pass.  Threads may return after the last
-// barrier.
-__device__ __attribute__((always_inline)) inline void epf_tile(const EpfArgs& a, int tbx, int tby) {
+// One 64x32 output tile of an EPF pass, up to each thread's filtered
+// samples; then epi(res, x, ys, nrows) consumes them: res[i][c] is channel c
+// of pixel (x, ys + i), i < nrows (nrows = 0 for a thread outside the
+// frame).  Every thread reaches the epilogue.  The epilogue may reuse s_q
+// (after a barrier) and s_w (the guide words are not read after stage B
+// unless guide_dbg is set) through the returned pointers.
+template <typename Epi>
+__device__ __attribute__((always_inline)) inline void epf_core(const EpfArgs& a, int tbx, int tby,
+                                                               Epi&& epi) {
   __shared__ uint4 s_q[kQH][kQW];
   __shared__ float2 s_r[kQH][kQW];
   __shared__ uint32_t s_w[3][kQH][kGW + 1];
@@ -1839,100 +1845,123 @@ __device__ __attribute__((always_inline)) inline void epf_tile(const EpfArgs& a,
   constexpr int R = kEpfRows;
   const int lx = tid & 63, row0 = R * (tid >> 6);
   const int x = x0 + lx, ys = y0 + row0;
-  if (x >= a.W || ys >= a.H) return;
-  const int nrows = min(R, a.H - ys);
+  const int nrows = x < a.W && ys < a.H ? min(R, a.H - ys) : 0;
   const int bi = (row0 >> 3) * 8 + (lx >> 3);  // the pixel's block in the tile
   const int mul64 = s_mul[bi];
-  float* o0 = a.out + size_t(ys) * a.stride + x;
   if (a.guide_dbg) {
     const int wg = (lx + 4) >> 2, sh = 8 * ((lx + 4) & 3);
     for (int i = 0; i < nrows; ++i)
       for (int c = 0; c < 3; ++c)
         a.guide_dbg[(size_t(c) * a.H + ys + i) * a.W + x] = uint8_t(s_w[c][row0 + 4 + i][wg] >> sh);
   }
-  if (mul64 > 0) {  // sigma < 16: the pass leaves the pixel unchanged
-    for (int i = 0; i < nrows; ++i) {
+  float res[R][3];
+  if (nrows == 0) {
+#pragma unroll
+    for (int i = 0; i < R; ++i)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) res[i][c] = 0.0f;
+  } else if (mul64 > 0) {  // sigma < 16: the pass leaves the pixel unchanged
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
       const int v = row0 + 4 + i;
-      o0[size_t(i) * a.stride] = __uint_as_float(s_q[v][lx + 3].w);
-      o0[plane + size_t(i) * a.stride] = s_r[v][lx + 3].x;
-      o0[2 * plane + size_t(i) * a.stride] = s_r[v][lx + 3].y;
+      res[i][0] = __uint_as_float(s_q[v][lx + 3].w);
+      res[i][1] = s_r[v][lx + 3].x;
+      res[i][2] = s_r[v][lx + 3].y;
     }
-    return;
-  }
-  const uint32_t thr = a.thr, smax = s_sadmax[bi];
-  uint32_t ref[R + 2][3];
+  } else {
+    const uint32_t thr = a.thr, smax = s_sadmax[bi];
+    uint32_t ref[R + 2][3];
 #pragma unroll
-  for (int j = 0; j < R + 2; ++j) {
-    const uint4 q = s_q[row0 + 3 + j][lx + 3];
-    ref[j][0] = q.x;
-    ref[j][1] = q.y;
-    ref[j][2] = q.z;
-  }
-  float acc[R][4];
+    for (int j = 0; j < R + 2; ++j) {
+      const uint4 q = s_q[row0 + 3 + j][lx + 3];
+      ref[j][0] = q.x;
+      ref[j][1] = q.y;
+      ref[j][2] = q.z;
+    }
+    float acc[R][4];
 #pragma unroll
-  for (int i = 0; i < R; ++i)
+    for (int i = 0; i < R; ++i)
 #pragma unroll
-    for (int c = 0; c < 4; ++c) acc[i][c] = 0.0f;
+      for (int c = 0; c < 4; ++c) acc[i][c] = 0.0f;
 
-  // The 56 window offsets; CLAMP (uniform over the workgroup) selects the
-  // form with the clamp at 507 and the threshold on the weight pattern, the
-  // other form thresholds the SAD itself (where it passes, it is below 507;
-  // where it does not, the unclamped product is discarded).
-  auto accumulate = [&](auto clamp_tag) {
-    constexpr bool CLAMP = decltype(clamp_tag)::value;
-    for (int cx = -3; cx <= 4; ++cx) {
-      // window column cx: guide words of cell rows row0 .. row0 + R + 7 and
-      // the input samples of rows row0 + 1 .. row0 + R + 6
-      uint4 nb[R + 8];
-      float2 in12[R + 6];
+    // The 56 window offsets; CLAMP (uniform over the workgroup) selects the
+    // form with the clamp at 507 and the threshold on the weight pattern, the
+    // other form thresholds the SAD itself (where it passes, it is below 507;
+    // where it does not, the unclamped product is discarded).
+    auto accumulate = [&](auto clamp_tag) {
+      constexpr bool CLAMP = decltype(clamp_tag)::value;
+      for (int cx = -3; cx <= 4; ++cx) {
+        // window column cx: guide words of cell rows row0 .. row0 + R + 7 and
+        // the input samples of rows row0 + 1 .. row0 + R + 6
+        uint4 nb[R + 8];
+        float2 in12[R + 6];
 #pragma unroll
-      for (int j = 0; j < R + 8; ++j) nb[j] = s_q[row0 + j][lx + 3 + cx];
+        for (int j = 0; j < R + 8; ++j) nb[j] = s_q[row0 + j][lx + 3 + cx];
 #pragma unroll
-      for (int j = 0; j < R + 6; ++j) in12[j] = s_r[row0 + 1 + j][lx + 3 + cx];
+        for (int j = 0; j < R + 6; ++j) in12[j] = s_r[row0 + 1 + j][lx + 3 + cx];
 #pragma unroll
-      for (int cy = -3; cy <= 3; ++cy) {
-        uint32_t rs[R + 2];
+        for (int cy = -3; cy <= 3; ++cy) {
+          uint32_t rs[R + 2];
 #pragma unroll
-        for (int j = 0; j < R + 2; ++j) {
-          const uint4 q = nb[j + cy + 3];
-          uint32_t t = __builtin_amdgcn_sad_u8(ref[j][0], q.x, 0u);
-          t = __builtin_amdgcn_sad_u8(ref[j][1], q.y, t);
-          rs[j] = __builtin_amdgcn_sad_u8(ref[j][2], q.z, t);
-        }
-#pragma unroll
-        for (int i = 0; i < R; ++i) {
-          const uint32_t sad = add3(rs[i], rs[i + 1], rs[i + 2]);
-          uint32_t wb;
-          if constexpr (CLAMP) {
-            const uint32_t t = uint32_t(__mul24(int(min(sad, 507u)), mul64)) + kEpfC;
-            wb = select_hi(thr, t, t);
-          } else {
-            const uint32_t t = uint32_t(__mul24(int(sad), mul64)) + kEpfC;
-            wb = select_hi(sad, smax, t);
+          for (int j = 0; j < R + 2; ++j) {
+            const uint4 q = nb[j + cy + 3];
+            uint32_t t = __builtin_amdgcn_sad_u8(ref[j][0], q.x, 0u);
+            t = __builtin_amdgcn_sad_u8(ref[j][1], q.y, t);
+            rs[j] = __builtin_amdgcn_sad_u8(ref[j][2], q.z, t);
           }
-          const float w = __uint_as_float(wb);
-          // the sample of pixel row i + cy: cell row row0 + 4 + i + cy
-          const int r = i + cy + 3;
-          acc[i][3] += w;
-          acc[i][0] = fmaf(w, __uint_as_float(nb[r + 1].w), acc[i][0]);
-          acc[i][1] = fmaf(w, in12[r].x, acc[i][1]);
-          acc[i][2] = fmaf(w, in12[r].y, acc[i][2]);
+#pragma unroll
+          for (int i = 0; i < R; ++i) {
+            const uint32_t sad = add3(rs[i], rs[i + 1], rs[i + 2]);
+            uint32_t wb;
+            if constexpr (CLAMP) {
+              const uint32_t t = uint32_t(__mul24(int(min(sad, 507u)), mul64)) + kEpfC;
+              wb = select_hi(thr, t, t);
+            } else {
+              const uint32_t t = uint32_t(__mul24(int(sad), mul64)) + kEpfC;
+              wb = select_hi(sad, smax, t);
+            }
+            const float w = __uint_as_float(wb);
+            // the sample of pixel row i + cy: cell row row0 + 4 + i + cy
+            const int r = i + cy + 3;
+            acc[i][3] += w;
+            acc[i][0] = fmaf(w, __uint_as_float(nb[r + 1].w), acc[i][0]);
+            acc[i][1] = fmaf(w, in12[r].x, acc[i][1]);
+            acc[i][2] = fmaf(w, in12[r].y, acc[i][2]);
+          }
         }
       }
-    }
-  };
-  if (s_clamp)
-    accumulate(std::true_type{});
-  else
-    accumulate(std::false_type{});
+    };
+    if (s_clamp)
+      accumulate(std::true_type{});
+    else
+      accumulate(std::false_type{});
+    // J.2.5 normalization; the weight total is in [1, 56] (the centre weight
+    // 1 always passes), so the hardware reciprocal (1 ulp) serves
 #pragma unroll
-  for (int i = 0; i < R; ++i)
+    for (int i = 0; i < R; ++i)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) res[i][c] = acc[i][c] * __builtin_amdgcn_rcpf(acc[i][3]);
+  }
+  epi(res, x, ys, nrows, &s_q[0][0], &s_w[0][0][0]);
+}
+
+// epf_core's epilogue storing the filtered samples to a.out.
+__device__ __attribute__((always_inline)) inline void epf_store(const EpfArgs& a,
+                                                                const float (&res)[kEpfRows][3],
+                                                                int x, int ys, int nrows) {
+  const size_t plane = size_t(a.H) * a.stride;
+  float* o0 = a.out + size_t(ys) * a.stride + x;
+#pragma unroll
+  for (int i = 0; i < kEpfRows; ++i)
     if (i < nrows)
 #pragma unroll
-      for (int c = 0; c < 3; ++c)
-        // J.2.5 normalization; the weight total is in [1, 56] (the centre
-        // weight 1 always passes), so the hardware reciprocal (1 ulp) serves
-        o0[c * plane + size_t(i) * a.stride] = acc[i][c] * __builtin_amdgcn_rcpf(acc[i][3]);
+      for (int c = 0; c < 3; ++c) o0[c * plane + size_t(i) * a.stride] = res[i][c];
+}
+
+// One EPF pass tile stored to a.out.
+__device__ __attribute__((always_inline)) inline void epf_tile(const EpfArgs& a, int tbx, int tby) {
+  epf_core(a, tbx, tby, [&](const float (&res)[kEpfRows][3], int x, int ys, int nrows, uint4*,
+                            uint32_t*) { epf_store(a, res, x, ys, nrows); });
 }
 
 // ---------------------------------------------------------------------------
@@ -2235,6 +2264,8 @@ struct FusedArgs {
   int tiles_x, tiles_y;
   int run;         // tiles per run, 1 .. kRunMax
   int runs_x;      // runs per tile row: ceil(tiles_x / run)
+  int group;       // tiles per seam-pass workgroup (a multiple of run), <= kRunMax
+  int groups_x;    // seam-pass workgroups per tile row: ceil(tiles_x / group)
 };
 
 // The finish step of tile (tx, ty), the tile's samples in coef.  When the
@@ -2412,26 +2443,31 @@ __device__ __attribute__((always_inline)) inline void fused_unit(const FusedArgs
   }
 }
 
-// The seam pass, one workgroup per run (tile row ty, run tr of it): the
-// horizontal seam along the run's top edge (the last row of the tile row
-// above and the first row of this one, over the run's columns) when there
-// is a tile row above, and the vertical seam along its left edge (the last
-// column of the run to the left and the first of this one, over the rows
-// that are not in a horizontal seam) when there is a run to the left.
-// Thread j takes column X0 + j of the horizontal seam (both its pixels)
-// and row j of the vertical one (both its pixels), reading its windows
-// straight from the seam records (neighbouring threads read neighbouring
-// samples, so the reads coalesce).
+// The seam pass, one workgroup per group of f.group tiles of a tile row:
+// the horizontal seam along the group's top edge (the last row of the tile
+// row above and the first row of this one, over the group's columns) when
+// there is a tile row above, and the vertical seam at each run start in the
+// group with a tile to its left (the last column of that tile and the first
+// of the run, over the rows that are not in a horizontal seam).  Thread j
+// takes column X0 + j of the horizontal seam (both its pixels) and row j mod
+// 32 of the vertical seam at the group's tile j / 32 (both its pixels),
+// reading its windows straight from the seam records (neighbouring threads
+// read neighbouring samples, so the reads coalesce); a workgroup has
+// 64 f.group threads.
 template <int FMT>
 __device__ inline void seam_pixels(const FusedArgs& f, int u, const float* __restrict__ thr,
                                    const uint8_t* __restrict__ start8) {
   using T = typename OutT<FMT>::T;
   const FinishArgs& a = f.fin;
   const int tid = threadIdx.x;
-  const int ty = u / f.runs_x, tr = u - ty * f.runs_x;
-  const int X0 = kRecTW * f.run * tr, X1 = min(X0 + kRecTW * f.run, a.W);
+  const int ty = u / f.groups_x, tg = (u - ty * f.groups_x) * f.group;
+  const int X0 = kRecTW * tg, X1 = min(X0 + kRecTW * f.group, a.W);
   const int y0 = kRecTH * ty, h = min(kRecTH, a.H - y0);
-  const bool hseam = ty > 0, vseam = X0 > 0;
+  // the vertical seam this thread takes: at the group's tile tb, if a run
+  // starts there with a tile to its left
+  const int tb = tg + (tid >> 5);
+  const bool hseam = ty > 0;
+  const bool vseam = tb > 0 && tb < f.tiles_x && tb % f.run == 0 && (tid >> 5) < f.group;
   const float* seam = f.seam;
   const size_t trow = size_t(f.tiles_x) * kSeamTileF;  // one tile row of records
   auto finish_px = [&](int gx, int gy, const float (&wu)[3][3], const float (&wm)[3][3],
@@ -2476,13 +2512,14 @@ __device__ inline void seam_pixels(const FusedArgs& f, int u, const float* __res
     finish_px(x, y0, w[1], w[2], w[3]);
   }
   if (vseam) {
-    // columns X0 - 2, X0 - 1 (records 2, 3 of the tile to the left, which
-    // is 64 columns wide) and X0, X0 + 1 (records 0, 1 of this tile; column
-    // 0 again when it is one column wide), rows mirrored inside the tile row
+    // columns XB - 2, XB - 1 (records 2, 3 of the tile to the left, which
+    // is 64 columns wide) and XB, XB + 1 (records 0, 1 of tile tb; column 0
+    // again when it is one column wide), rows mirrored inside the tile row
     const int ya = hseam ? 1 : 0, yb = ty + 1 < f.tiles_y ? h - 1 : h;
-    const int y = ya + tid;
+    const int y = ya + (tid & 31);
+    const int XB = kRecTW * tb;
     if (y < yb) {
-      const int tx = X0 / kRecTW, w1 = min(kRecTW, a.W - X0) == 1 ? 0 : kSeamColF;
+      const int tx = tb, w1 = min(kRecTW, a.W - XB) == 1 ? 0 : kSeamColF;
       const float* lf = seam + size_t(ty) * trow + size_t(tx - 1) * kSeamTileF + 4 * kSeamRowF;
       const float* rt = lf + kSeamTileF;
       float w[3][4][3];  // [window row][column X0 - 2 ..][channel]
@@ -2508,7 +2545,7 @@ __device__ inline void seam_pixels(const FusedArgs& f, int u, const float* __res
             wm[c][d] = w[1][q0 + d][c];
             wd[c][d] = w[2][q0 + d][c];
           }
-        finish_px(X0 - 1 + q0, y0 + y, wu, wm, wd);
+        finish_px(XB - 1 + q0, y0 + y, wu, wm, wd);
       }
     }
   }
@@ -2521,14 +2558,146 @@ __device__ __attribute__((always_inline)) inline void seam_unit(const FusedArgs&
   if (fmt == JXLR_OUT_F32) {
     seam_pixels<JXLR_OUT_F32>(f, u, nullptr, nullptr);
   } else if (fmt == JXLR_OUT_U8_SRGB) {
-    for (int i = threadIdx.x; i < 257; i += kSeamThreads) s_thr[i] = f.fin.thr[i];
-    for (int i = threadIdx.x; i < kSrgbBucketsPadded / 4; i += kSeamThreads)
+    for (int i = threadIdx.x; i < 257; i += blockDim.x) s_thr[i] = f.fin.thr[i];
+    for (int i = threadIdx.x; i < kSrgbBucketsPadded / 4; i += blockDim.x)
       s_start[i] = reinterpret_cast<const uint32_t*>(f.fin.start8)[i];
     __syncthreads();
     seam_pixels<JXLR_OUT_U8_SRGB>(f, u, s_thr, reinterpret_cast<const uint8_t*>(s_start));
   } else {
     seam_pixels<JXLR_OUT_U16_SRGB>(f, u, f.fin.thr, nullptr);
   }
+}
+
+// ---------------------------------------------------------------------------
+// The finish fused into a frame's last EPF pass.  When nothing comes between
+// the EPF passes and the finish (no quantization constraint, patches, dots,
+// splines or noise), the last pass's output need not pass through HBM: the
+// EPF workgroup writes its filtered tile into LDS (over its staging cells,
+// which stage E no longer reads), finishes there the pixels whose Gaborish
+// window lies in the tile, and writes the samples along each side that
+// faces another tile into the tile's seam record; the seam pass (runs of
+// one tile) finishes the rest.  Every pixel goes through the finish's
+// operations in the same order, so the output equals that of the pass
+// followed by the finish bit for bit.
+struct EpfFinish {
+  FinishArgs fin;
+  float* seam;  // kSeamTileF floats per tile, tiles in row order
+  int tiles_x, tiles_y;
+};
+
+// Rows of a tile per wave in the EPF-fused finish (eight waves).
+constexpr int kEpfFinRows = kRecTH / (kEpfThreads / 64);
+static_assert(kEpfFinRows == 4, "EPF tile rows per wave");
+static_assert(sizeof(float) * 3 * kRecTH * kRecLd <= sizeof(uint4) * kQH * kQW,
+              "the filtered tile fits over the staging cells");
+static_assert(sizeof(float) * 257 + kSrgbBucketsPadded <= sizeof(uint32_t) * 3 * kQH * (kGW + 1),
+              "the 8-bit code tables fit over the guide words");
+
+template <int FMT>
+__device__ __attribute__((always_inline)) inline void epf_finish_tile(
+    const EpfFinish& e, float (*tile)[kRecTH][kRecLd], int tx, int ty,
+    const float* __restrict__ thr, const uint8_t* __restrict__ start8) {
+  using T = typename OutT<FMT>::T;
+  const FinishArgs& a = e.fin;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int x0 = kRecTW * tx, y0 = kRecTH * ty;
+  const int w = min(kRecTW, a.W - x0), h = min(kRecTH, a.H - y0);
+  const bool up = ty > 0, down = ty + 1 < e.tiles_y;
+  const bool left = tx > 0, right = tx + 1 < e.tiles_x;
+  float* rec = e.seam + (size_t(ty) * e.tiles_x + tx) * kSeamTileF;
+  // seam records: waves 0-3 the row records (lane = column), waves 4-5 the
+  // column records (thread = record, row)
+  if (wave < 4) {
+    const int r = wave, y = r < 2 ? r : h - 4 + r;
+    if ((r < 2 ? up : down) && lane < w && y >= 0 && y < h) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) rec[r * kSeamRowF + c * kRecTW + lane] = tile[c][y][lane];
+    }
+  } else if (wave < 6) {
+    const int i = tid - 256, q = i >> 5, y = i & 31;
+    const int x = q < 2 ? q : w - 4 + q;
+    if ((q < 2 ? left : right) && y < h && x >= 0 && x < w) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) rec[4 * kSeamRowF + q * kSeamColF + c * kRecTH + y] = tile[c][y][x];
+    }
+  }
+  // lane l takes column x0 + l of rows 4 wave ..: every column but the
+  // first (last) when a tile lies to the left (right), which are seams;
+  // window columns mirrored at the frame's edges
+  const bool col = lane < w && !(lane == 0 && left) && !(lane == w - 1 && right);
+  const int cm = min(max(mirror(x0 + lane - 1, a.W) - x0, 0), kRecTW - 1);
+  const int cp = min(max(mirror(x0 + lane + 1, a.W) - x0, 0), kRecTW - 1);
+  auto rowidx = [&](int r) { return min(max(mirror(y0 + r, a.H) - y0, 0), h - 1); };
+  auto load_row = [&](int r, float (&wv)[3][3]) {
+    const int yy = rowidx(r);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      wv[c][0] = tile[c][yy][cm];
+      wv[c][1] = tile[c][yy][lane];
+      wv[c][2] = tile[c][yy][cp];
+    }
+  };
+  T* out[3] = {static_cast<T*>(a.out[0]), static_cast<T*>(a.out[1]), static_cast<T*>(a.out[2])};
+  const int r0 = kEpfFinRows * wave;
+  float wv[3][3][3];
+  load_row(r0 - 1, wv[0]);
+  load_row(r0, wv[1]);
+#pragma unroll
+  for (int i = 0; i < kEpfFinRows; ++i) {
+    const int r = r0 + i, u = i % 3, m = (i + 1) % 3, d = (i + 2) % 3;
+    load_row(r + 1, wv[d]);
+    if (col && r < h && !((r == 0 && up) || (r == h - 1 && down))) {
+      float v[3];
+      if (a.gab) {
+        gab_pixel(a, wv[u], wv[m], wv[d], v);
+      } else {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) v[c] = wv[m][c][1];
+      }
+      float rgb[3];
+      xyb_to_rgb(a, v, rgb);
+      const size_t o = size_t(y0 + r) * a.out_stride + x0 + lane;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) out[c][o] = encode_out<FMT>(rgb[c], thr, start8);
+    }
+  }
+}
+
+// epf_core's epilogue with the finish fused (EpfFinish e) for tile (tx, ty).
+__device__ __attribute__((always_inline)) inline void epf_fin_epilogue(
+    const EpfFinish& e, int tx, int ty, const float (&res)[kEpfRows][3], int nrows, uint4* sq,
+    uint32_t* sw) {
+    const int tid = threadIdx.x, lx = tid & 63, row0 = kEpfRows * (tid >> 6);
+    float (*tile)[kRecTH][kRecLd] = reinterpret_cast<float (*)[kRecTH][kRecLd]>(sq);
+    float* s_thr = reinterpret_cast<float*>(sw);
+    uint8_t* s_start = reinterpret_cast<uint8_t*>(sw + 257);
+    const int fmt = e.fin.format;
+    __syncthreads();  // stage E's reads of the staging cells are done
+#pragma unroll
+    for (int i = 0; i < kEpfRows; ++i)
+      if (i < nrows)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) tile[c][row0 + i][lx] = res[i][c];
+    if (fmt == JXLR_OUT_U8_SRGB) {
+      for (int i = tid; i < 257; i += kEpfThreads) s_thr[i] = e.fin.thr[i];
+      for (int i = tid; i < kSrgbBucketsPadded / 4; i += kEpfThreads)
+        reinterpret_cast<uint32_t*>(s_start)[i] = reinterpret_cast<const uint32_t*>(e.fin.start8)[i];
+    }
+    __syncthreads();
+    if (fmt == JXLR_OUT_F32)
+      epf_finish_tile<JXLR_OUT_F32>(e, tile, tx, ty, nullptr, nullptr);
+    else if (fmt == JXLR_OUT_U8_SRGB)
+      epf_finish_tile<JXLR_OUT_U8_SRGB>(e, tile, tx, ty, s_thr, s_start);
+    else
+      epf_finish_tile<JXLR_OUT_U16_SRGB>(e, tile, tx, ty, e.fin.thr, nullptr);
+}
+
+// The EPF pass of tile (tx, ty) with the finish fused.
+__device__ __attribute__((always_inline)) inline void epf_fin_tile(const EpfArgs& a,
+                                                                   const EpfFinish& e, int tx,
+                                                                   int ty) {
+  epf_core(a, tx, ty, [&](const float (&res)[kEpfRows][3], int, int, int nrows, uint4* sq,
+                          uint32_t* sw) { epf_fin_epilogue(e, tx, ty, res, nrows, sq, sw); });
 }
 
 // ---------------------------------------------------------------------------
@@ -3207,6 +3376,11 @@ __global__ __launch_bounds__(kEpfThreads, kEpfMinBlocks) void epf_kernel(EpfArgs
   const int t = xcd_tile(blockIdx.x, gridDim.x);
   epf_tile(a, t % tiles_x, t / tiles_x);
 }
+__global__ __launch_bounds__(kEpfThreads, kEpfMinBlocks) void epf_fin_kernel(EpfArgs a,
+                                                                             EpfFinish e) {
+  const int t = xcd_tile(blockIdx.x, gridDim.x);
+  epf_fin_tile(a, e, t % e.tiles_x, t / e.tiles_x);
+}
 template <bool NOISE>
 __global__ __launch_bounds__(fin_threads<kFinRowsFrame>()) void finish_kernel(FinishArgs a,
                                                                               int tiles_x) {
@@ -3240,6 +3414,10 @@ struct FrameDesc {
   FinishArgs fin;  // reads the XYB buffer the last stage before it wrote
   int epf_iters;
   int tiles_x;     // 64x32 tiles per row
+  int tiles_y;
+  int fin_in_epf;  // the finish is fused into the last EPF pass (seam records
+                   // in `seam`; the seam stage finishes the rest)
+  float* seam;
 };
 
 struct BatchArgs {
@@ -3330,14 +3508,33 @@ __global__ __launch_bounds__(kEpfThreads, kEpfMinBlocks) void epf_batch_kernel(B
       const int lt = __builtin_amdgcn_readfirstlane(r.t - b.tile_start[f]);
       const int tx = const_load(&d->tiles_x);
       // the pass's arguments are staged in LDS (a private copy of this
-      // structure would be kept in scratch memory)
+      // structure would be kept in scratch memory), and for the last pass of
+      // a frame with the finish fused, the finish's
       __shared__ EpfArgs s_args;
-      static_assert(sizeof(EpfArgs) % 4 == 0, "word copy");
+      __shared__ EpfFinish s_fin;
+      static_assert(sizeof(EpfArgs) % 4 == 0 && sizeof(FinishArgs) % 4 == 0, "word copy");
+      static_assert(sizeof(EpfArgs) / 4 + sizeof(FinishArgs) / 4 <= kEpfThreads, "one word each");
+      const bool fin = b.pass + 1 == const_load(&d->epf_iters) && const_load(&d->fin_in_epf);
       if (threadIdx.x < sizeof(EpfArgs) / 4)
         reinterpret_cast<uint32_t*>(&s_args)[threadIdx.x] =
             reinterpret_cast<const uint32_t*>(&d->epf[b.pass])[threadIdx.x];
+      else if (fin && threadIdx.x < sizeof(EpfArgs) / 4 + sizeof(FinishArgs) / 4)
+        reinterpret_cast<uint32_t*>(&s_fin.fin)[threadIdx.x - sizeof(EpfArgs) / 4] =
+            reinterpret_cast<const uint32_t*>(&d->fin)[threadIdx.x - sizeof(EpfArgs) / 4];
+      if (fin && threadIdx.x == 0) {
+        s_fin.seam = d->seam;
+        s_fin.tiles_x = tx;
+        s_fin.tiles_y = d->tiles_y;
+      }
       __syncthreads();
-      epf_tile(s_args, lt % tx, lt / tx);
+      const int tbx = lt % tx, tby = lt / tx;
+      epf_core(s_args, tbx, tby, [&](const float (&res)[kEpfRows][3], int x, int ys, int nrows,
+                                     uint4* sq, uint32_t* sw) {
+        if (fin)
+          epf_fin_epilogue(s_fin, tbx, tby, res, nrows, sq, sw);
+        else
+          epf_store(s_args, res, x, ys, nrows);
+      });
     }
     if (!PERSIST) break;
   }
@@ -3351,6 +3548,10 @@ __global__ __launch_bounds__(fin_threads<kFinRowsBatch>()) void finish_batch_ker
     if (PERSIST) __syncthreads();
     const int f = __builtin_amdgcn_readfirstlane(b.tile_frame[r.t]);
     const FrameDesc* d = b.frames + f;
+    if (const_load(&d->fin_in_epf)) {  // finished in its last EPF pass
+      if (!PERSIST) break;
+      continue;
+    }
     const int lt = __builtin_amdgcn_readfirstlane(r.t - b.tile_start[f]);
     const int tx = const_load(&d->tiles_x);
     const FinishArgs a = const_load(&d->fin);
@@ -3721,14 +3922,19 @@ int tiles_y(const jxlr_frame_params* p) { return int((p->ysize + kRecTH - 1) / k
 int regions_of(const jxlr_frame_params* p) {
   return ((blocks_of(p->xsize) + 3) / 4) * ((blocks_of(p->ysize) + 3) / 4);
 }
-// Whether the frame's reconstruction goes to the finish unchanged (no EPF
-// pass and none of patches, dots, splines, noise), so that the fused kernel
-// takes both and no XYB frame is stored.
-bool fused_path(const jxlr_frame_params* p) {
-  return p->fuse >= 0 && p->epf_iters == 0 && !p->noise && p->num_patches == 0 &&
+// Whether the finish is fused into the stage before it: nothing comes
+// between the reconstruction or the last EPF pass and the finish (no
+// quantization constraint, patches, dots, splines or noise).
+bool finish_fused(const jxlr_frame_params* p) {
+  return p->fuse >= 0 && !(p->qco && p->epf_iters > 0) && !p->noise && p->num_patches == 0 &&
          p->num_dots == 0 && p->num_splines == 0;
 }
-// Seam records of the fused path: one per tile.
+// The reconstruction fused with the finish (no EPF pass): no XYB frame is
+// stored.
+bool fused_path(const jxlr_frame_params* p) { return finish_fused(p) && p->epf_iters == 0; }
+// The finish fused into the last EPF pass.
+bool epf_fin(const jxlr_frame_params* p) { return finish_fused(p) && p->epf_iters > 0; }
+// Seam records of a fused finish: one per tile.
 size_t seam_bytes(const jxlr_frame_params* p) {
   return round256(size_t(tiles_x(p)) * tiles_y(p) * kSeamTileF * sizeof(float));
 }
@@ -3785,7 +3991,7 @@ struct FrameBuffers {
 size_t frame_ws_bytes(const jxlr_frame_params* p) {
   return info_bytes(p) + xyb_buffers(p) * xyb_bytes(p) + pred_bytes(p) +
          (p->noise ? xyb_bytes(p) : 0) + (gab_pass(p) ? xyb_bytes(p) : 0) + spline_bytes(p) +
-         (fused_path(p) ? seam_bytes(p) : 0);
+         (finish_fused(p) ? seam_bytes(p) : 0);
 }
 
 FrameBuffers frame_buffers(const jxlr_frame_params* p, char* base) {
@@ -3807,7 +4013,7 @@ FrameBuffers frame_buffers(const jxlr_frame_params* p, char* base) {
     b.spline = t;
     t += spline_bytes(p);
   }
-  if (fused_path(p)) b.seam = reinterpret_cast<float*>(t);
+  if (finish_fused(p)) b.seam = reinterpret_cast<float*>(t);
   const bool qco = p->qco && p->epf_iters > 0;
   float* cur = b.buf[0];
   for (int it = 0; it < p->epf_iters; ++it) {
@@ -3835,7 +4041,7 @@ size_t jxlr_spline_scratch_bytes(const jxlr_frame_params* p) {
 }
 
 size_t jxlr_seam_bytes(const jxlr_frame_params* p) {
-  if (check_params(p) != JXLR_OK || !fused_path(p)) return 0;
+  if (check_params(p) != JXLR_OK || !finish_fused(p)) return 0;
   return seam_bytes(p);
 }
 
@@ -4033,7 +4239,37 @@ jxlr_status make_fused_args(jxlr_ctx* ctx, const jxlr_frame_params* p, const jxl
   f.tiles_y = tiles_y(p);
   f.run = run;
   f.runs_x = (f.tiles_x + run - 1) / run;
+  f.group = run;
+  f.groups_x = f.runs_x;
   *res = f;
+  return JXLR_OK;
+}
+
+// The finish fused into the last EPF pass: its finish arguments and seam
+// records (e), and the seam pass's (runs of one tile, f).
+jxlr_status make_epf_finish(jxlr_ctx* ctx, const jxlr_frame_params* p, const jxlr_frame_io* io,
+                            float* seam, size_t seam_len, EpfFinish* e, FusedArgs* f) {
+  if (!epf_fin(p)) return JXLR_E_PARAM;
+  if (!seam) return JXLR_E_NULL;
+  if (seam_len < seam_bytes(p)) return JXLR_E_WORKSPACE;
+  EpfFinish ef{};
+  jxlr_status st = make_finish_args(ctx, p, io, nullptr, p->xsize, &ef.fin);
+  if (st) return st;
+  ef.seam = seam;
+  ef.tiles_x = tiles_x(p);
+  ef.tiles_y = tiles_y(p);
+  FusedArgs fa{};
+  fa.fin = ef.fin;
+  fa.seam = seam;
+  fa.tiles_x = ef.tiles_x;
+  fa.tiles_y = ef.tiles_y;
+  fa.run = 1;
+  fa.runs_x = ef.tiles_x;
+  // the seam pass takes kRunMax tiles per workgroup (a vertical seam at each)
+  fa.group = kRunMax;
+  fa.groups_x = (ef.tiles_x + kRunMax - 1) / kRunMax;
+  *e = ef;
+  *f = fa;
   return JXLR_OK;
 }
 
@@ -4360,6 +4596,29 @@ jxlr_status jxlr_finish(jxlr_ctx* ctx, const jxlr_frame_params* p, const jxlr_fr
   return launch_status(hipGetLastError());
 }
 
+jxlr_status jxlr_epf_finish(jxlr_ctx* ctx, const jxlr_frame_params* p, const jxlr_frame_io* io,
+                            const uint8_t* info, const float* xyb_in, size_t xyb_stride,
+                            float* seam, size_t seam_len, hipStream_t stream) {
+  if (!ctx || !xyb_in) return JXLR_E_NULL;
+  jxlr_status st = check_params(p);
+  if (st) return st;
+  EpfArgs a;
+  EpfFinish e;
+  FusedArgs f;
+  if ((st = make_epf_finish(ctx, p, io, seam, seam_len, &e, &f))) return st;
+  // the pass's output buffer is not written; the input names a valid one
+  if ((st = make_epf_args(ctx, p, io, info, xyb_in, const_cast<float*>(xyb_in), xyb_stride,
+                          nullptr, nullptr, &a)))
+    return st;
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return JXLR_E_HIP;
+  const int n = e.tiles_x * e.tiles_y;
+  hipLaunchKernelGGL(epf_fin_kernel, dim3(n), dim3(kEpfThreads), 0, stream, a, e);
+  if (n > 1)
+    hipLaunchKernelGGL(seam_kernel, dim3(f.groups_x * f.tiles_y), dim3(kSeamThreads), 0, stream, f);
+  return launch_status(hipGetLastError());
+}
+
 jxlr_status jxlr_reconstruct_finish(jxlr_ctx* ctx, const jxlr_frame_params* p,
                                     const jxlr_frame_io* io, const uint8_t* info, float* seam,
                                     size_t seam_len, hipStream_t stream) {
@@ -4376,7 +4635,8 @@ jxlr_status jxlr_reconstruct_finish(jxlr_ctx* ctx, const jxlr_frame_params* p,
     hipLaunchKernelGGL(fused_kernel<true>, grid, dim3(kRecThreads), 0, stream, f);
   else
     hipLaunchKernelGGL(fused_kernel<false>, grid, dim3(kRecThreads), 0, stream, f);
-  if (grid.x > 1) hipLaunchKernelGGL(seam_kernel, grid, dim3(kSeamThreads), 0, stream, f);
+  if (grid.x > 1)
+    hipLaunchKernelGGL(seam_kernel, dim3(f.groups_x * f.tiles_y), dim3(kSeamThreads), 0, stream, f);
   return launch_status(hipGetLastError());
 }
 
@@ -4397,10 +4657,14 @@ jxlr_status jxlr_decode(jxlr_ctx* ctx, const jxlr_frame_params* p, const jxlr_fr
   if (fused_path(p))
     return jxlr_reconstruct_finish(ctx, p, &iop, b.info, b.seam, seam_bytes(p), stream);
   if ((st = jxlr_reconstruct(ctx, p, &iop, b.info, b.buf[0], stride, stream))) return st;
-  for (int it = 0; it < p->epf_iters; ++it)
+  const bool fin = epf_fin(p);
+  for (int it = 0; it < p->epf_iters - (fin ? 1 : 0); ++it)
     if ((st = jxlr_epf_pass(ctx, p, io, b.info, b.epf_in[it], b.epf_out[it], stride, nullptr,
                             nullptr, stream)))
       return st;
+  if (fin)
+    return jxlr_epf_finish(ctx, p, &iop, b.info, b.epf_in[p->epf_iters - 1], stride, b.seam,
+                           seam_bytes(p), stream);
   if (p->qco && p->epf_iters > 0 &&
       (st = jxlr_qco_pass(ctx, p, io, b.info, b.buf[0], b.post, stride, stream)))
     return st;
@@ -4639,8 +4903,8 @@ bool takes_opt(const jxlr_frame_params* p, int k) {
     case JXLR_STAGE_GABORISH: return gab_pass(p);
     case JXLR_STAGE_DOTS: return p->num_dots > 0;
     case JXLR_STAGE_SPLINES: return p->num_splines > 0;
-    case JXLR_STAGE_FUSED:
-    case JXLR_STAGE_SEAM: return fused_path(p);
+    case JXLR_STAGE_FUSED: return fused_path(p);
+    case JXLR_STAGE_SEAM: return finish_fused(p);
   }
   return false;
 }
@@ -4914,10 +5178,16 @@ jxlr_status jxlr_batch_prepare(jxlr_ctx* ctx, int n, const jxlr_frame_params* p,
         case JXLR_STAGE_FUSED:
         case JXLR_STAGE_SEAM: {
           FusedArgs a;
-          if (!(st = make_fused_args(ctx, &p[i], &iop, fb.info, fb.seam, seam_bytes(&p[i]),
-                                     p[i].fuse > 0 ? p[i].fuse : run, &a))) {
-            put_entry(hdr, at, a, a.runs_x);
-            units = a.runs_x * a.tiles_y;
+          EpfFinish e;
+          if (fused)
+            st = make_fused_args(ctx, &p[i], &iop, fb.info, fb.seam, seam_bytes(&p[i]),
+                                 p[i].fuse > 0 ? p[i].fuse : run, &a);
+          else
+            st = make_epf_finish(ctx, &p[i], &iop, fb.seam, seam_bytes(&p[i]), &e, &a);
+          if (!st) {
+            const int per_row = JXLR_STAGE_PRED + k == JXLR_STAGE_FUSED ? a.runs_x : a.groups_x;
+            put_entry(hdr, at, a, per_row);
+            units = per_row * a.tiles_y;
           }
           break;
         }
@@ -4929,6 +5199,9 @@ jxlr_status jxlr_batch_prepare(jxlr_ctx* ctx, int n, const jxlr_frame_params* p,
     if (st) return st;
     d.epf_iters = p[i].epf_iters;
     d.tiles_x = tiles_x(&p[i]);
+    d.tiles_y = tiles_y(&p[i]);
+    d.fin_in_epf = epf_fin(&p[i]);
+    d.seam = fb.seam;
     const long long nt = (long long)tstart[i] + (fused ? 0 : tiles_x(&p[i]) * tiles_y(&p[i]));
     if (nt > INT32_MAX / 2) return JXLR_E_SIZE;
     tstart[i + 1] = int(nt);
@@ -4984,12 +5257,12 @@ jxlr_status jxlr_batch_run(jxlr_ctx* ctx, const jxlr_batch_plan* plan,
   if ((st = launch_stage(ctx, plan, JXLR_STAGE_INFO, c.grid_info, 0, 0, stream))) return st;
   if ((st = launch_stage(ctx, plan, JXLR_STAGE_PRED, 0, 0, 0, stream))) return st;
   if ((st = launch_stage(ctx, plan, JXLR_STAGE_FUSED, 0, 0, 0, stream))) return st;
-  if ((st = launch_stage(ctx, plan, JXLR_STAGE_SEAM, 0, 0, 0, stream))) return st;
   if ((st = launch_stage(ctx, plan, JXLR_STAGE_RECON, c.grid_recon, c.order_recon, 0, stream)))
     return st;
   for (int k = 0; k < plan->max_epf_iters; ++k)
     if ((st = launch_stage(ctx, plan, JXLR_STAGE_EPF, c.grid_epf, c.order_epf, k, stream)))
       return st;
+  if ((st = launch_stage(ctx, plan, JXLR_STAGE_SEAM, 0, 0, 0, stream))) return st;
   for (int s = JXLR_STAGE_QCO; s <= JXLR_STAGE_SPLINES; ++s)
     if ((st = launch_stage(ctx, plan, s, 0, 0, 0, stream))) return st;
   return launch_stage(ctx, plan, JXLR_STAGE_FINISH, c.grid_finish, c.order_finish, 0, stream);

@@ -218,6 +218,8 @@ _SIGS = {
     "jxlr_finish": ([C.c_void_p, C.POINTER(FrameParams), C.POINTER(FrameIO), C.c_void_p,
                      C.c_size_t, C.c_void_p], C.c_int),
     "jxlr_seam_bytes": ([C.POINTER(FrameParams)], C.c_size_t),
+    "jxlr_epf_finish": ([C.c_void_p, C.POINTER(FrameParams), C.POINTER(FrameIO), C.c_void_p,
+                         C.c_void_p, C.c_size_t, C.c_void_p, C.c_size_t, C.c_void_p], C.c_int),
     "jxlr_reconstruct_finish": ([C.c_void_p, C.POINTER(FrameParams), C.POINTER(FrameIO),
                                  C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p], C.c_int),
     "jxlr_batch_workspace_bytes": ([C.c_int, C.POINTER(FrameParams)], C.c_size_t),
@@ -590,6 +592,16 @@ class Context:
                                              C.byref(df.io(out, ac_pred=pred)), info.data_ptr(),
                                              seam.data_ptr(), seam.numel(),
                                              _stream_handle(stream)), "reconstruct_finish")
+
+    def epf_finish(self, p, df, info, xyb_in, out, seam=None, stream=None):
+        """The last EPF pass and the finish without storing the pass's output
+        (frames with nothing between the two)."""
+        if seam is None:
+            seam = self.seam_buffer(p)
+        _check(lib().jxlr_epf_finish(self.handle, C.byref(p), C.byref(df.io(out)),
+                                     info.data_ptr(), xyb_in.data_ptr(), xyb_in.shape[2],
+                                     seam.data_ptr(), seam.numel(), _stream_handle(stream)),
+               "epf_finish")
 
     def qco_pass(self, p, df, info, xyb_orig, xyb_io, stream=None):
         _check(lib().jxlr_qco_pass(self.handle, C.byref(p), C.byref(df.io()), info.data_ptr(),

@@ -226,10 +226,10 @@ def test_autotune_and_stages(ctx, tmp_path):
     _fill(outs)
     ctx.batch_stage(plan, J.STAGE_INFO, 0, 0, 0)
     ctx.batch_stage(plan, J.STAGE_FUSED, 0, 0, 0)
-    ctx.batch_stage(plan, J.STAGE_SEAM, 0, 0, 0)
     ctx.batch_stage(plan, J.STAGE_RECON, cfg.grid_recon, cfg.order_recon, 0)
     for k in range(plan.max_epf_iters):
         ctx.batch_stage(plan, J.STAGE_EPF, cfg.grid_epf, cfg.order_epf, k)
+    ctx.batch_stage(plan, J.STAGE_SEAM, 0, 0, 0)
     ctx.batch_stage(plan, J.STAGE_FINISH, cfg.grid_finish, cfg.order_finish, 0)
     torch.cuda.synchronize()
     for i, (o, r) in enumerate(zip(outs, ref)):

@@ -1,12 +1,14 @@
-"""GPU tests of the reconstruction fused with the finish (frames with no EPF
-pass, patches, dots, splines or noise): jxlr_reconstruct_finish, jxlr_decode
-and the batch's FUSED and SEAM stages must equal the separate
-reconstruction and finish stages bit for bit (every pixel goes through the
-same operations in the same order), over ragged sizes (tiles cut by the
-frame edge, frames one pixel wide or high), every run length (seams between
-runs and between tile rows), every output format, Gaborish on and off, the
-split-precision transform, AC prediction and DC smoothing, and ill-formed
-regions; and the fused output against the FP64 oracle.
+"""GPU tests of the fused finish: the reconstruction fused with the finish
+(frames with no EPF pass, patches, dots, splines or noise) and the finish
+fused into the last EPF pass (frames with EPF passes and nothing between the
+last one and the finish).  jxlr_reconstruct_finish, jxlr_epf_finish,
+jxlr_decode and the batch's FUSED, EPF and SEAM stages must equal the
+separate stages bit for bit (every pixel goes through the same operations in
+the same order), over ragged sizes (tiles cut by the frame edge, frames one
+pixel wide or high), every run length (seams between runs and between tile
+rows), every output format, Gaborish on and off, the split-precision
+transform, AC prediction and DC smoothing, and ill-formed regions; and the
+fused output against the FP64 oracle.
 """
 import numpy as np
 import pytest
@@ -205,3 +207,123 @@ def test_batch_all_fused(ctx):
     torch.cuda.synchronize()
     for i, (o, r) in enumerate(zip(outs, refs)):
         np.testing.assert_array_equal(o.cpu().numpy(), r, err_msg=f"frame {i}")
+
+
+# ---- the finish fused into the last EPF pass ---------------------------------
+
+EPF_SIZES = [(1, 1), (1, 70), (70, 1), (2, 2), (63, 31), (64, 32), (65, 33), (128, 32), (127, 95),
+             (200, 136), (300, 97), (577, 70)]
+
+
+@pytest.mark.parametrize("W,H", EPF_SIZES)
+@pytest.mark.parametrize("epf", [1, 2, 3])
+def test_epf_finish_equals_stages(ctx, W, H, epf):
+    from paper_1908_03565_amd import jxlr as J
+    f = wl.frame(W, H, seed=11 * W + H + epf, epf_iters=epf)
+    df = J.DeviceFrame(f)
+    ref = _staged(ctx, _params(f, epf_iters=epf, fuse=-1), df)
+    np.testing.assert_array_equal(_decoded(ctx, _params(f, epf_iters=epf), df), ref)
+    assert ctx.device_status() == 0
+
+
+@pytest.mark.parametrize("fmt", [F32, U8, U16])
+@pytest.mark.parametrize("gab", [0, 1])
+def test_epf_finish_formats_and_gaborish(ctx, fmt, gab):
+    import torch
+    from paper_1908_03565_amd import jxlr as J
+    f = wl.frame(333, 161, seed=700 + 10 * fmt + gab, epf_iters=2, gab=gab)
+    df = J.DeviceFrame(f)
+    p = _params(f, fmt, epf_iters=2)
+    ref = _staged(ctx, _params(f, fmt, epf_iters=2, fuse=-1), df)
+    np.testing.assert_array_equal(_decoded(ctx, p, df), ref)
+    # the stage entry point: the first pass apart, then the fused last pass
+    info = ctx.empty_info(p)
+    ctx.block_info(p, df, info)
+    xyb = ctx.empty_xyb(p)
+    ctx.reconstruct(p, df, info, xyb)
+    mid = ctx.empty_xyb(p)
+    ctx.epf_pass(p, df, info, xyb, mid)
+    out = ctx.empty_out(p)
+    out.fill_(9)
+    ctx.epf_finish(p, df, info, mid, out)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(out.cpu().numpy(), ref)
+
+
+@pytest.mark.parametrize("opt", ["split", "acpred", "smooth", "mixed_tiling", "ill_formed"])
+def test_epf_finish_options(ctx, opt):
+    from paper_1908_03565_amd import jxlr as J
+    kw, fkw = {}, {}
+    if opt == "split":
+        kw = dict(idct_split=1)
+        fkw = dict(choices=[wl.DCT8, wl.DCT16, wl.DCT32, wl.DCT16X8])
+    elif opt == "acpred":
+        kw = dict(ac_prediction=1)
+    elif opt == "smooth":
+        kw = dict(dc_smoothing=1)
+    elif opt == "mixed_tiling":
+        fkw = dict(tiling="mixed")
+    f = wl.frame(401, 229, seed=811, epf_iters=1, **fkw)
+    if opt == "ill_formed":
+        f["strategy"][:] = wl.DCT8
+        f["strategy"][4, 5] = wl.DCT16
+    df = J.DeviceFrame(f)
+    ref = _staged(ctx, _params(f, epf_iters=1, fuse=-1, **kw), df)
+    np.testing.assert_array_equal(_decoded(ctx, _params(f, epf_iters=1, **kw), df), ref)
+    assert ctx.device_status() == (10 if opt == "ill_formed" else 0)
+
+
+def test_epf_finish_not_taken_with_constraint_or_noise(ctx):
+    """With the quantization constraint or noise after the passes the finish
+    stays apart (no seam records), and the result still equals the stages."""
+    from paper_1908_03565_amd import jxlr as J
+    f = wl.frame(150, 90, seed=5, epf_iters=2)
+    df = J.DeviceFrame(f)
+    for kw in (dict(qco=1), dict(noise=1, noise_lut=[0.05] * 16)):
+        p = _params(f, epf_iters=2, **kw)
+        assert J.lib().jxlr_seam_bytes(J.C.byref(p)) == 0
+        np.testing.assert_array_equal(_decoded(ctx, p, df), _staged(ctx, p, df))
+
+
+def test_batch_epf_finish_mix(ctx):
+    """A batch of frames finished in their last EPF pass (one to three
+    passes, three formats), fused reconstructions and frames with the
+    constraint (finished apart) equals each frame through the stages alone;
+    graph replays too."""
+    import torch
+    from paper_1908_03565_amd import jxlr as J
+    specs = [(256, 256, 1, U8, {}), (300, 97, 2, F32, {}), (1, 70, 3, U16, {}),
+             (577, 70, 1, U8, dict(ac_prediction=1)), (200, 136, 0, F32, {}),
+             (130, 66, 2, F32, dict(qco=1)), (65, 33, 1, U16, {}), (64, 32, 2, U8, dict(fuse=-1))]
+    ps, dfs, outs, refs = [], [], [], []
+    for i, (W, H, epf, fmt, kw) in enumerate(specs):
+        f = wl.frame(W, H, seed=1900 + i, epf_iters=epf)
+        df = J.DeviceFrame(f)
+        p = _params(f, fmt, epf_iters=epf, **kw)
+        refs.append(_staged(ctx, _params(f, fmt, epf_iters=epf, **dict(kw, fuse=-1)), df))
+        ps.append(p)
+        dfs.append(df)
+        outs.append(ctx.empty_out(p))
+    ios = [df.io(o) for df, o in zip(dfs, outs)]
+    ws = ctx.batch_workspace(ps)
+    plan = ctx.batch_prepare(ps, ios, ws)
+    # seam stage: the fused reconstruction and the five frames finished in
+    # their last pass
+    assert plan.opt_frames[J.STAGE_SEAM - J.STAGE_PRED] == 6
+    for run in range(2):
+        for o in outs:
+            o.fill_(run + 3)
+        ctx.batch_run(plan)
+        torch.cuda.synchronize()
+        for i, (o, r) in enumerate(zip(outs, refs)):
+            np.testing.assert_array_equal(o.cpu().numpy(), r, err_msg=f"run {run} frame {i}")
+    g = ctx.graph(plan)
+    for rep in range(3):
+        for o in outs:
+            o.fill_(rep + 1)
+        torch.cuda.synchronize()
+        g.launch()
+        torch.cuda.synchronize()
+        for i, (o, r) in enumerate(zip(outs, refs)):
+            np.testing.assert_array_equal(o.cpu().numpy(), r, err_msg=f"replay {rep} frame {i}")
+    assert ctx.device_status() == 0

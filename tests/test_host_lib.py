@@ -144,21 +144,25 @@ def test_workspace_bytes():
     seam = J.lib().jxlr_seam_bytes(C.byref(p))
     assert seam == 4 * (4 * 3 * 64 + 4 * 3 * 32) * 4
     assert fused == 256 + seam
+    # with EPF passes: two XYB plane sets, plus the seam records when the
+    # finish is fused into the last pass (nothing between the two)
     p1 = J.params(100, 50, epf_iters=1)
     xyb = (3 * 100 * 50 * 4 + 255) // 256 * 256
-    assert J.workspace_bytes(p1) == 256 + 2 * xyb
-    assert J.lib().jxlr_seam_bytes(C.byref(p1)) == 0
+    assert J.workspace_bytes(p1) == 256 + 2 * xyb + seam
+    assert J.lib().jxlr_seam_bytes(C.byref(p1)) == seam
     p2 = J.params(100, 50, epf_iters=2)
     assert J.workspace_bytes(p2) == J.workspace_bytes(p1) and J.workspace_bytes(p2) % 256 == 0
     # the quantization constraint keeps the reconstruction past a second
-    # pass: one more plane set then, none with a single pass or none at all
-    assert J.workspace_bytes(J.params(100, 50, epf_iters=2, qco=1)) == J.workspace_bytes(p2) + xyb
-    assert J.workspace_bytes(J.params(100, 50, epf_iters=1, qco=1)) == J.workspace_bytes(p2)
+    # pass: one more plane set then, none with a single pass or none at all;
+    # and the finish stays apart (no seam records)
+    assert J.workspace_bytes(J.params(100, 50, epf_iters=2, qco=1)) == 256 + 3 * xyb
+    assert J.workspace_bytes(J.params(100, 50, epf_iters=1, qco=1)) == 256 + 2 * xyb
     assert J.workspace_bytes(J.params(100, 50, epf_iters=0, qco=1)) == fused
-    # noise adds the pseudorandom channels, one plane set (and, without EPF
-    # passes, takes the unfused path: one reconstruction plane set)
-    assert J.workspace_bytes(J.params(100, 50, epf_iters=2, noise=1)) - J.workspace_bytes(p2) == xyb
+    # noise adds the pseudorandom channels, one plane set (and keeps the
+    # finish apart: one reconstruction plane set without EPF passes)
+    assert J.workspace_bytes(J.params(100, 50, epf_iters=2, noise=1)) == 256 + 3 * xyb
     assert J.workspace_bytes(J.params(100, 50, epf_iters=0, noise=1)) == 256 + 2 * xyb
+    assert J.workspace_bytes(J.params(100, 50, epf_iters=2, fuse=-1)) == 256 + 2 * xyb
     # fuse = -1 keeps the reconstruction and the finish apart: one plane set
     assert J.workspace_bytes(J.params(100, 50, epf_iters=0, fuse=-1)) == 256 + xyb
     for bad in (-2, 5):
@@ -169,7 +173,9 @@ def test_workspace_bytes():
     assert 12 * 4 * 13 * 7 <= extra < 12 * 4 * 13 * 7 + 256
     # dots or splines: Gaborish into a plane set of its own; splines add
     # their curve samples (3 doubles, 16 per control point)
-    gp = J.params(100, 50, epf_iters=2, gab=1)
+    # (frames with dots or splines keep the finish apart: the base is the
+    # unfused layout)
+    gp = J.params(100, 50, epf_iters=2, gab=1, fuse=-1)
     base = J.workspace_bytes(gp)
     assert J.workspace_bytes(J.params(100, 50, epf_iters=2, gab=1, num_dots=5)) - base == xyb
     sp = J.params(100, 50, epf_iters=2, gab=1, num_splines=3, num_spline_points=40)
@@ -177,7 +183,8 @@ def test_workspace_bytes():
     assert 3 * 16 * 8 * 40 <= sb < 3 * 16 * 8 * 40 + 256 and sb % 256 == 0
     assert J.workspace_bytes(sp) - base == xyb + sb
     sp0 = J.params(100, 50, epf_iters=2, gab=0, num_splines=3, num_spline_points=40)
-    assert J.workspace_bytes(sp0) - J.workspace_bytes(J.params(100, 50, epf_iters=2, gab=0)) == sb
+    assert J.workspace_bytes(sp0) - J.workspace_bytes(J.params(100, 50, epf_iters=2, gab=0,
+                                                               fuse=-1)) == sb
     assert J.lib().jxlr_spline_scratch_bytes(C.byref(gp)) == 0
 
 
