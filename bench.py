@@ -178,7 +178,7 @@ def bench_frame(args, J, wl, torch, np):
     p = J.params(W, H, out_format=frame["out_format"], idct_split=int(args.split), qco=qco,
                  ac_prediction=acp, noise=nz, noise_lut=nlut, num_patches=args.patches,
                  num_dots=args.dots, dot_colour_quant=dcq, num_splines=args.splines,
-                 num_spline_points=nsp, **frame["params"])
+                 num_spline_points=nsp, fuse=-1 if args.no_fuse else 0, **frame["params"])
     st = J.validate_maps_host(p, frame)
     assert st == 0, st
     ctx = J.Context(0)
@@ -194,6 +194,12 @@ def bench_frame(args, J, wl, torch, np):
     out = ctx.empty_out(p)
     stream = torch.cuda.current_stream()
     n_epf = p.epf_iters
+    # the finish fused into the stage before it (as jxlr_decode runs it):
+    # nothing between the last EPF pass (or the reconstruction) and the
+    # finish; the finish event then closes an empty interval
+    fused_fin = p.fuse >= 0 and not qco and not nz and not (args.patches or args.dots or
+                                                           args.splines)
+    seam = ctx.seam_buffer(p) if fused_fin else None
 
     def step(evs):
         # block info + reconstruct -> EPF passes (-> quantization constraint)
@@ -206,12 +212,18 @@ def bench_frame(args, J, wl, torch, np):
             evs[1].record(stream)
             ctx.ac_prediction(p, df, info, pred, stream=stream)
             evs[2].record(stream)
-        ctx.reconstruct(p, df, info, bufs[0], stream=stream, pred=pred)
+        if fused_fin and n_epf == 0:
+            ctx.reconstruct_finish(p, df, info, out, seam=seam, stream=stream, pred=pred)
+        else:
+            ctx.reconstruct(p, df, info, bufs[0], stream=stream, pred=pred)
         evs[o + 1].record(stream)
         cur = 0
         for i in range(n_epf):
             dst = (2 if i & 1 else 1) if qco else 1 - cur
-            ctx.epf_pass(p, df, info, bufs[cur], bufs[dst], stream=stream)
+            if fused_fin and i == n_epf - 1:
+                ctx.epf_finish(p, df, info, bufs[cur], out, seam=seam, stream=stream)
+            else:
+                ctx.epf_pass(p, df, info, bufs[cur], bufs[dst], stream=stream)
             cur = dst
             evs[o + 2 + i].record(stream)
         if qco:
@@ -233,7 +245,8 @@ def bench_frame(args, J, wl, torch, np):
         if nz:
             ctx.noise_channels(p, raw, stream=stream)
             evs[-2].record(stream)
-        ctx.finish(p, df, src, out, stream=stream, noise_raw=raw)
+        if not fused_fin:
+            ctx.finish(p, df, src, out, stream=stream, noise_raw=raw)
         evs[-1].record(stream)
 
     o = 2 * acp
@@ -280,13 +293,31 @@ def bench_frame(args, J, wl, torch, np):
         + (f"patches/dots/splines {feat_ms:.4f} ms, " if pd else "")
         + (f"noise channels {noise_ms:.4f} ms, " if nz else "") + f"finish {fin_ms:.4f} ms")
 
-    kernels = kernel_table(W * H, recon_ms, statistics.mean(epf_ms) if n_epf else None, fin_ms,
-                           p.out_format, ("recon_kernel", "epf_kernel", "finish_kernel"))
+    if fused_fin:
+        # the finish runs inside the last EPF pass (epf_fin_kernel and the
+        # seam pass) or the reconstruction (fused_kernel and the seam pass):
+        # the table holds the plain passes and the fused stage
+        kernels = {}
+        if n_epf:
+            kernels["recon_kernel"] = dict(ms=recon_ms, bound="hbm", bytes_per_px=RECON_BYTES_PER_PX,
+                                           achieved=W * H * RECON_BYTES_PER_PX / (recon_ms / 1e3) / 1e9)
+            plain = epf_ms[:-1] or epf_ms
+            kernels["epf_kernel"] = dict(ms=statistics.mean(plain), bound="alu",
+                                         achieved=W * H * EPF_OPS_PER_PX / (statistics.mean(plain) / 1e3) / 1e12)
+        else:
+            fb = FUSED_BYTES_PER_PX[p.out_format]
+            kernels["fused_kernel"] = dict(ms=recon_ms, bound="hbm", bytes_per_px=fb,
+                                           achieved=W * H * fb / (recon_ms / 1e3) / 1e9)
+        n_plain = max(n_epf - 1, 1)
+    else:
+        kernels = kernel_table(W * H, recon_ms, statistics.mean(epf_ms) if n_epf else None, fin_ms,
+                               p.out_format, ("recon_kernel", "epf_kernel", "finish_kernel"))
+        n_plain = n_epf
     wname = (frame["name"] + ("_qco" if qco else "") + ("_acpred" if acp else "")
              + ("_noise" if nz else "") + (f"_patches{args.patches}" if args.patches else "")
              + (f"_dots{args.dots}" if args.dots else "")
              + (f"_splines{args.splines}" if args.splines else ""))
-    roofline = roofline_of(kernels, {"epf_kernel": n_epf}, wname, W * H)
+    roofline = roofline_of(kernels, {"epf_kernel": n_plain}, wname, W * H)
 
     graph_lat = None
     if args.workload == "c1":
@@ -384,7 +415,9 @@ def bench_frame(args, J, wl, torch, np):
                      **({"ac_prediction": round(pred_ms, 5)} if acp else {}),
                      **({"noise_channels": round(noise_ms, 5)} if nz else {}),
                      **({"patches_gaborish_dots_splines": round(feat_ms, 5)} if pd else {}),
-                     "finish": round(fin_ms, 5)},
+                     "finish": round(fin_ms, 5),
+                     **({"finish_fused_into": "last EPF pass" if n_epf else "reconstruction"}
+                        if fused_fin else {})},
         "host_wall_ms_per_step": round(wall / args.steps * 1e3, 5),
         "error": err,
         "roofline": roofline,
