@@ -3273,10 +3273,19 @@ struct NoiseArgs {
   int W, H;
   float* raw;  // [3][H][W]
   const DeviceTables* __restrict__ tab;
+  // unit layout: full-width (256-sample) groups per group row, their
+  // octets, whether a narrower group ends each row, group rows
+  int gxf, oct, part, gy;
 };
 
-constexpr int kNoiseRows = 16;
-constexpr int kNoiseThreads = 8 * (256 / kNoiseRows);
+// Rows per run: a workgroup (one wave) takes a run of kNoiseRows rows of one
+// channel for eight groups of one group row (lanes: 8 generators x 8
+// groups) or for the narrower group at the row's end.  The groups of a unit
+// share their size, so the generators' common jump-ahead is uniform across
+// the wave.
+constexpr int kNoiseRows = 4;
+constexpr int kNoiseThreads = 64;
+constexpr int kNoiseRuns = 256 / kNoiseRows;  // runs of a whole group
 
 __device__ inline uint64_t splitmix64(uint64_t z) {
   z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
@@ -3284,52 +3293,68 @@ __device__ inline uint64_t splitmix64(uint64_t z) {
   return z ^ (z >> 31);
 }
 
-__device__ __attribute__((always_inline)) inline void noise_group(const NoiseArgs& a, int blk,
-                                                                  int groups_x) {
-  const int c = blk % 3, g = blk / 3;
-  const int x0 = 256 * (g % groups_x), y0 = 256 * (g / groups_x);
-  const int gw = min(256, a.W - x0), gh = min(256, a.H - y0);
-  const int lane = threadIdx.x & 7, r0 = kNoiseRows * (threadIdx.x >> 3);
-  if (r0 >= gh) return;
+__device__ __attribute__((always_inline)) inline void noise_unit(const NoiseArgs& a, int u) {
+  // the jump map of the current power as nibble images (8 KB)
+  __shared__ uint4 s_nib[32][16];
+  const int cu_n = a.oct + a.part;
+  const int c = u % 3, rest = u / 3;
+  const int rr = rest / cu_n, cu = rest - rr * cu_n;
+  // group rows before the last are whole: kNoiseRuns runs each
+  const int gy = min(rr / kNoiseRuns, a.gy - 1);
+  const int r0 = kNoiseRows * (rr - kNoiseRuns * gy);
+  const int lane = threadIdx.x & 63, g = lane & 7, k = lane >> 3;
+  const bool partial = cu == a.oct;
+  const int gx = partial ? a.gxf : 8 * cu + k;
+  const bool valid = partial ? k == 0 : gx < a.gxf;
+  const int x0 = 256 * gx, y0 = 256 * gy;
+  const int gw = partial ? a.W - 256 * a.gxf : 256, gh = min(256, a.H - y0);
   const int nseg = (gw + 15) / 16;
-  // generator `lane`: first word s1, second word s0 of the seeding chain
+  // generator g of the group: first word s1, second word s0 of the seeding
+  // chain
   const uint64_t seed = (uint64_t(uint32_t(y0)) << 32) + uint64_t(uint32_t(x0));
   uint64_t s0 = splitmix64(seed + 0x9E3779B97F4A7C15ull);
   uint64_t s1 = splitmix64(s0);
-  for (int i = 1; i <= lane; ++i) {
+  for (int i = 1; i <= g; ++i) {
     s0 = splitmix64(s1);
     s1 = splitmix64(s0);
   }
   uint64_t A = s1, B = s0;
-  // jump to step (c gh + r0) nseg: the 2^k-th power of the step map for each
-  // set bit k
+  // jump to step (c gh + r0) nseg, the same for every lane: the 2^k-th power
+  // of the step map for each set bit k, its table staged in LDS
   const uint32_t t0 = uint32_t((c * gh + r0) * nseg);
   const DeviceTables* __restrict__ T = a.tab;
-  for (int k = 0; k < 14; ++k) {
-    if (!((t0 >> k) & 1u)) continue;
-    uint64_t na = 0, nb = 0;
-#pragma unroll 8
-    for (int r = 0; r < 64; ++r) {
-      const uint32_t pa = uint32_t(__popcll(T->noise_jump[k][r][0] & A) +
-                                   __popcll(T->noise_jump[k][r][1] & B)) & 1u;
-      const uint32_t pb = uint32_t(__popcll(T->noise_jump[k][64 + r][0] & A) +
-                                   __popcll(T->noise_jump[k][64 + r][1] & B)) & 1u;
-      na |= uint64_t(pa) << r;
-      nb |= uint64_t(pb) << r;
+  for (int kk = 0; kk < 14; ++kk) {
+    if (!((t0 >> kk) & 1u)) continue;
+    __syncthreads();
+    const uint4* src = reinterpret_cast<const uint4*>(&T->noise_nib[kk][0][0][0]);
+#pragma unroll
+    for (int i = 0; i < 32 * 16 / kNoiseThreads; ++i)
+      (&s_nib[0][0])[lane + kNoiseThreads * i] = src[lane + kNoiseThreads * i];
+    __syncthreads();
+    uint32_t n0 = 0, n1 = 0, n2 = 0, n3 = 0;
+#pragma unroll
+    for (int p = 0; p < 32; ++p) {
+      const uint64_t w = p < 16 ? A : B;
+      const uint4 e = s_nib[p][(w >> (4 * (p & 15))) & 15u];
+      n0 ^= e.x;
+      n1 ^= e.y;
+      n2 ^= e.z;
+      n3 ^= e.w;
     }
-    A = na;
-    B = nb;
+    A = (uint64_t(n1) << 32) | n0;
+    B = (uint64_t(n3) << 32) | n2;
   }
+  if (!valid) return;
   const int r1 = min(r0 + kNoiseRows, gh);
   for (int r = r0; r < r1; ++r) {
     float* row = a.raw + (size_t(c) * a.H + y0 + r) * a.W + x0;
     for (int sg = 0; sg < nseg; ++sg) {
-      const uint64_t u = A ^ (A << 23);
-      const uint64_t out = u + B;
-      const uint64_t nb = u ^ B ^ (u >> 18) ^ (B >> 5);
+      const uint64_t uu = A ^ (A << 23);
+      const uint64_t out = uu + B;
+      const uint64_t nb = uu ^ B ^ (uu >> 18) ^ (B >> 5);
       A = B;
       B = nb;
-      const int x = 16 * sg + 2 * lane;
+      const int x = 16 * sg + 2 * g;
       // binary32 with exponent 0 and the top 23 bits as mantissa, minus 1
       if (x < gw) row[x] = __uint_as_float((uint32_t(out) >> 9) | 0x3F800000u) - 1.0f;
       if (x + 1 < gw) row[x + 1] = __uint_as_float((uint32_t(out >> 32) >> 9) | 0x3F800000u) - 1.0f;
@@ -3398,8 +3423,8 @@ __global__ __launch_bounds__(256) void dots_kernel(DotArgs a) { dots_block(a, bl
 __global__ __launch_bounds__(kSplineThreads) void spline_kernel(SplineArgs a) {
   spline_one(a, blockIdx.x);
 }
-__global__ __launch_bounds__(kNoiseThreads) void noise_kernel(NoiseArgs a, int groups_x) {
-  noise_group(a, blockIdx.x, groups_x);
+__global__ __launch_bounds__(kNoiseThreads) void noise_kernel(NoiseArgs a) {
+  noise_unit(a, blockIdx.x);
 }
 
 // The batch kernels share one tile list over reconstruction, EPF and finish.
@@ -3626,8 +3651,7 @@ __global__ __launch_bounds__(256) void patches_batch_kernel(OptBatch ob) {
 __global__ __launch_bounds__(kNoiseThreads) void noise_batch_kernel(OptBatch ob) {
   NoiseArgs a;
   int row;
-  const int u = opt_unit(ob, a, row);
-  noise_group(a, u, row);
+  noise_unit(a, opt_unit(ob, a, row));
 }
 __global__ __launch_bounds__(256) void gaborish_batch_kernel(OptBatch ob) {
   GabArgs a;
@@ -4442,10 +4466,20 @@ jxlr_status make_noise_args(jxlr_ctx* ctx, const jxlr_frame_params* p, float* ra
   if (!ctx || !raw) return JXLR_E_NULL;
   jxlr_status st = check_params(p);
   if (st) return st;
-  *out = NoiseArgs{int(p->xsize), int(p->ysize), raw, ctx->tables};
-  const int gx = int((p->xsize + 255) / 256), gy = int((p->ysize + 255) / 256);
-  *row = gx;
-  *units = 3 * gx * gy;
+  NoiseArgs a{int(p->xsize), int(p->ysize), raw, ctx->tables, 0, 0, 0, 0};
+  a.gxf = a.W / 256;
+  a.oct = (a.gxf + 7) / 8;
+  a.part = a.W % 256 != 0;
+  a.gy = (a.H + 255) / 256;
+  // runs: kNoiseRuns per whole group row, then the last row's
+  const int last_h = a.H - 256 * (a.gy - 1);
+  const long long runs =
+      (long long)kNoiseRuns * (a.gy - 1) + (last_h + kNoiseRows - 1) / kNoiseRows;
+  const long long n = 3LL * (a.oct + a.part) * runs;
+  if (n > INT32_MAX / 2) return JXLR_E_SIZE;
+  *out = a;
+  *row = a.oct + a.part;
+  *units = int(n);
   return JXLR_OK;
 }
 
@@ -4562,7 +4596,7 @@ jxlr_status jxlr_noise_channels(jxlr_ctx* ctx, const jxlr_frame_params* p, float
   if (st) return st;
   DeviceGuard g(ctx->device);
   if (!g.ok) return JXLR_E_HIP;
-  hipLaunchKernelGGL(noise_kernel, dim3(units), dim3(kNoiseThreads), 0, stream, a, gx);
+  hipLaunchKernelGGL(noise_kernel, dim3(units), dim3(kNoiseThreads), 0, stream, a);
   return launch_status(hipGetLastError());
 }
 

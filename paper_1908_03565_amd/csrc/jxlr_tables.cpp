@@ -659,10 +659,23 @@ bool build_tables(DeviceTables* t, const DequantEncoding* enc) {
       }
     }
     for (int k = 0; k < 14; ++k) {
-      for (int r = 0; r < 128; ++r) {
-        t->noise_jump[k][r][0] = m[r][0];
-        t->noise_jump[k][r][1] = m[r][1];
-      }
+      // column j of m (the image of unit state j), then the XOR of the
+      // columns of each nibble value
+      uint64_t col[128][2] = {};
+      for (int r = 0; r < 128; ++r)
+        for (int j = 0; j < 128; ++j)
+          if ((m[r][j >> 6] >> (j & 63)) & 1u) col[j][r >> 6] |= uint64_t(1) << (r & 63);
+      for (int p = 0; p < 32; ++p)
+        for (int v = 0; v < 16; ++v) {
+          uint64_t w0 = 0, w1 = 0;
+          for (int b = 0; b < 4; ++b)
+            if ((v >> b) & 1) {
+              w0 ^= col[4 * p + b][0];
+              w1 ^= col[4 * p + b][1];
+            }
+          t->noise_nib[k][p][v][0] = w0;
+          t->noise_nib[k][p][v][1] = w1;
+        }
       // m = m * m over GF(2): row r of the product is the XOR of the rows j
       // of m selected by the bits of row r
       uint64_t sq[128][2] = {};

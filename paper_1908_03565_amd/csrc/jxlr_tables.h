@@ -108,10 +108,11 @@ struct DeviceTables {
   float pred_s8_1;
   // Noise (K.5.2): jump-ahead of one XorShift128+ generator, whose 128-bit
   // state (bits 0-63 the first word, 64-127 the second) advances by a map
-  // linear over GF(2); noise_jump[k][r] holds row r of that map's 2^k-th
-  // power (bit r of the advanced state is the parity of the row ANDed with
-  // the state), as two words.
-  uint64_t noise_jump[14][128][2];
+  // linear over GF(2).  noise_nib[k][p][v] is the image under that map's
+  // 2^k-th power of the state whose nibble p (bits 4p .. 4p + 3) is v and
+  // whose other bits are 0, as two words; the image of a state is the XOR
+  // of the entries its 32 nibbles select.
+  uint64_t noise_nib[14][32][16][2];
   // Splines (K.4): DCTScale(k) of ContinuousIDCT, D(32, k) of I.2.6.1 times
   // 1 / (4 sqrt 2) at k = 0 and 1/4 elsewhere, in binary64.
   double spline_scale[32];

@@ -40,6 +40,6 @@ const float* shim_pred_u() { return &g_tables.pred_u[0][0][0]; }
 const float* shim_pred_v() { return &g_tables.pred_v[0][0][0]; }
 float shim_pred_sf() { return g_tables.pred_sf; }
 float shim_pred_s8_1() { return g_tables.pred_s8_1; }
-const uint64_t* shim_noise_jump() { return &g_tables.noise_jump[0][0][0]; }
+const uint64_t* shim_noise_nib() { return &g_tables.noise_nib[0][0][0][0]; }
 const double* shim_spline_scale() { return g_tables.spline_scale; }
 }

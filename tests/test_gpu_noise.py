@@ -18,7 +18,7 @@ def ctx():
     return J.Context(0)
 
 
-@pytest.mark.parametrize("W,H", [(256, 256), (600, 300), (37, 530), (1, 1)])
+@pytest.mark.parametrize("W,H", [(256, 256), (600, 300), (37, 530), (1, 1), (2400, 300)])
 def test_noise_channels_bit_exact(ctx, W, H):
     import torch
     from paper_1908_03565_amd import jxlr as J

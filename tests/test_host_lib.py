@@ -224,7 +224,7 @@ def shim(tmp_path_factory):
               "shim_dqs", "shim_a16s", "shim_a32s", "shim_b16s", "shim_b32s", "shim_pred_u",
               "shim_pred_v"):
         getattr(L, f).restype = C.POINTER(C.c_float)
-    L.shim_noise_jump.restype = C.POINTER(C.c_uint64)
+    L.shim_noise_nib.restype = C.POINTER(C.c_uint64)
     L.shim_pred_sf.restype = C.c_float
     L.shim_pred_s8_1.restype = C.c_float
     L.shim_spline_scale.restype = C.POINTER(C.c_double)
@@ -431,15 +431,6 @@ def test_ac_prediction_tables_match_oracle(shim):
     assert shim.shim_pred_s8_1() == pytest.approx(_col_scale(8)[1], rel=1e-7)
 
 
-def _gf2_apply(rows, a, b):
-    # rows: (128, 2) uint64; state (a, b) -> (a', b')
-    out = [0, 0]
-    for r in range(128):
-        par = (bin(int(rows[r, 0]) & a).count("1") + bin(int(rows[r, 1]) & b).count("1")) & 1
-        out[r >> 6] |= par << (r & 63)
-    return out[0], out[1]
-
-
 def test_spline_scale_table(shim):
     # DCTScale(k) of K.4: the oracle's ContinuousIDCT of a unit coefficient
     # at t = -1/2, where every cosine is 1
@@ -450,21 +441,32 @@ def test_spline_scale_table(shim):
         assert got[k] == pytest.approx(O.spline_idct(e, -0.5), rel=1e-15, abs=0)
 
 
+def _nib_apply(T, a, b):
+    # T: (32, 16, 2) uint64; state (a, b) -> XOR of the entries its nibbles select
+    o0 = o1 = 0
+    for p in range(32):
+        v = ((a if p < 16 else b) >> (4 * (p % 16))) & 15
+        o0 ^= int(T[p, v, 0])
+        o1 ^= int(T[p, v, 1])
+    return o0, o1
+
+
 def test_noise_jump_tables(shim):
     # power 0 is one generator step (first word a, second b: a' = b,
     # b' = u ^ b ^ (u >> 18) ^ (b >> 5), u = a ^ (a << 23)); each power is the
-    # square of the one before
+    # square of the one before; the entry of nibble value 0 is 0
     M = 2 ** 64 - 1
-    J = np.ctypeslib.as_array(shim.shim_noise_jump(), shape=(14 * 128 * 2,)).reshape(14, 128, 2)
+    T = np.ctypeslib.as_array(shim.shim_noise_nib(), shape=(14 * 32 * 16 * 2,)).reshape(14, 32, 16, 2)
+    assert not T[:, :, 0, :].any()
     rng = np.random.default_rng(9)
     for _ in range(4):
         a, b = (int(v) for v in rng.integers(0, 2 ** 63, size=2, dtype=np.int64))
         a |= 1 << 63
         u = (a ^ (a << 23)) & M
-        assert _gf2_apply(J[0], a, b) == (b, (u ^ b ^ (u >> 18) ^ (b >> 5)) & M)
+        assert _nib_apply(T[0], a, b) == (b, (u ^ b ^ (u >> 18) ^ (b >> 5)) & M)
         for k in (0, 5, 12):
-            twice = _gf2_apply(J[k], *_gf2_apply(J[k], a, b))
-            assert twice == _gf2_apply(J[k + 1], a, b), k
+            twice = _nib_apply(T[k], *_nib_apply(T[k], a, b))
+            assert twice == _nib_apply(T[k + 1], a, b), k
 
 
 def test_schedule_cache_roundtrip(tmp_path):
