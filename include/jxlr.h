@@ -190,11 +190,13 @@ typedef struct {
    * least one each, at most 2^22 in all); it sizes the curve scratch. */
   int32_t  num_splines;
   int32_t  num_spline_points;
-  /* The reconstruction fused with the finish (jxlr_reconstruct_finish) for a
-   * frame that qualifies (no EPF pass, patches, dots, splines or noise):
-   * 0 (the default) lets the library choose the tiles per run, 1..4 sets
-   * them, -1 keeps the two stages apart (jxlr_decode then stores the XYB
-   * frame in its workspace).  The output does not depend on it. */
+  /* The finish fused into the stage before it, for a frame that qualifies
+   * (no patches, dots, splines or noise, no quantization constraint after
+   * EPF passes): into the reconstruction (jxlr_reconstruct_finish) when the
+   * frame has no EPF pass, else into the last EPF pass (jxlr_epf_finish).
+   * 0 (the default) lets the library choose the reconstruction's tiles per
+   * run, 1..4 sets them, -1 keeps the stages apart (jxlr_decode then stores
+   * the XYB frame in its workspace).  The output does not depend on it. */
   int32_t  fuse;
 } jxlr_frame_params;
 

@@ -1672,7 +1672,12 @@ constexpr int kEpfTW = 64, kEpfTH = 32;  // output tile
 // Output rows per EPF thread; a tile takes 64 * 32 / kEpfRows threads.
 constexpr int kEpfRows = 4;
 constexpr int kEpfThreads = kEpfTW * kEpfTH / kEpfRows;
-constexpr int kEpfMinBlocks = 2;
+// Two workgroups per CU (the LDS allows two): the second launch bound below
+// is in waves per SIMD, two workgroups of eight waves over four SIMDs, which
+// caps the registers at 128 (the persistent batch form's loop over tiles
+// would otherwise hold hoisted values in up to 247).
+constexpr int kEpfBlocksPerCU = 2;
+constexpr int kEpfWavesPerSimd = kEpfBlocksPerCU * kEpfThreads / 256;
 constexpr int kQW = 72, kQH = 40;  // cells per row (start columns x0-4..), rows y0-4..
 constexpr int kGW = 19;            // packed guide words per row: columns x0-4..x0+71
 
@@ -1702,7 +1707,11 @@ __device__ __attribute__((always_inline)) inline void epf_core(const EpfArgs& a,
   __shared__ uint8_t s_owner[2][16], s_strat[2][16];
   __shared__ int s_bad[2];
 
-  const int tid = threadIdx.x;
+  // opaque to the optimizer: in the persistent form's loop over tiles,
+  // values derived from the thread index would be hoisted out of it and
+  // held in registers across the whole loop
+  int tid = threadIdx.x;
+  asm volatile("" : "+v"(tid));
   const int x0 = kEpfTW * tbx, y0 = kEpfTH * tby;
   const int gbx0 = x0 / 8, gby0 = y0 / 8;
   const size_t plane = size_t(a.H) * a.stride;
@@ -2254,8 +2263,6 @@ constexpr int kSeamColF = 3 * kRecTH;
 constexpr int kSeamTileF = 4 * kSeamRowF + 4 * kSeamColF;
 constexpr int kRunMax = 4;  // tiles per run at most
 constexpr int kSeamThreads = kRunMax * kRecTW;  // a thread per column of a run
-// Rows of a tile per wave in the fused finish: three waves cover 32 rows.
-constexpr int kFusedRows = (kRecTH + kRecThreads / 64 - 1) / (kRecThreads / 64);
 
 struct FusedArgs {
   ReconArgs rec;   // rec.xyb is not used
@@ -2268,16 +2275,22 @@ struct FusedArgs {
   int groups_x;    // seam-pass workgroups per tile row: ceil(tiles_x / group)
 };
 
-// The finish step of tile (tx, ty), the tile's samples in coef.  When the
-// tile is not the first of its run, the tile before it left its last two
-// columns in carry and its last column also in coef's column -1.  first /
-// last: the tile starts / ends its run.
-template <int FMT>
+// The finish step of tile (tx, ty), the tile's samples in coef, by NT
+// threads (the reconstruction's 192 or the EPF's 512).  When the tile is
+// not the first of its run, the tile before it left its last two columns in
+// carry and its last column also in coef's column -1.  first / last: the
+// tile starts / ends its run.  s_bad (may be null): the regions whose
+// samples count as zero.  F: FusedArgs or EpfFinish (fin, seam, tiles_x,
+// tiles_y).
+template <int FMT, int NT, typename F>
 __device__ __attribute__((always_inline)) inline void fused_tile(
-    const FusedArgs& f, float (*coef)[kRecTH][kRecLd], const int* s_bad,
+    const F& f, float (*coef)[kRecTH][kRecLd], const int* s_bad,
     float (*carry)[kRecTH][2], int tx, int ty, bool first, bool last,
     const float* __restrict__ thr, const uint8_t* __restrict__ start8) {
   using T = typename OutT<FMT>::T;
+  // rows per wave of the main pass
+  constexpr int kRows = (kRecTH + NT / 64 - 1) / (NT / 64);
+  static_assert(NT >= 4 * kRecTH && NT % 64 == 0, "record copies and strips");
   const FinishArgs& a = f.fin;
   int tid = threadIdx.x;  // recomputed per tile, as in recon_core
   asm volatile("" : "+v"(tid));
@@ -2285,8 +2298,8 @@ __device__ __attribute__((always_inline)) inline void fused_tile(
   const int x0 = kRecTW * tx, y0 = kRecTH * ty;
   const int w = min(kRecTW, a.W - x0), h = min(kRecTH, a.H - y0);
   // an ill-formed region's samples are zero, as the reconstruction stores them
-  if (s_bad[0] | s_bad[1]) {
-    for (int i = tid; i < 3 * kRecTH * kRecTW; i += kRecThreads) {
+  if (s_bad && (s_bad[0] | s_bad[1])) {
+    for (int i = tid; i < 3 * kRecTH * kRecTW; i += NT) {
       const int x = i & 63, y = (i >> 6) & 31, c = i >> 11;
       if (s_bad[x >> 5]) coef[c][y][x] = 0.0f;
     }
@@ -2299,7 +2312,7 @@ __device__ __attribute__((always_inline)) inline void fused_tile(
   // seam records: wave k copies row records k (and k + 3), lane = column;
   // the first 128 threads copy the column records, thread = (record, row)
   if (up || down) {
-    for (int r = wave; r < 4; r += kRecThreads / 64) {
+    for (int r = wave; r < 4; r += NT / 64) {
       const int y = r < 2 ? r : h - 4 + r;
       if ((r < 2 ? up : down) && lane < w && y >= 0 && y < h) {
 #pragma unroll
@@ -2353,7 +2366,7 @@ __device__ __attribute__((always_inline)) inline void fused_tile(
     finish_px(x0 - 1, tid, wv[0], wv[1], wv[2]);
   }
 
-  // Lane l takes column x0 + l of rows kFusedRows * wave ..: every column
+  // Lane l takes column x0 + l of rows kRows * wave ..: every column
   // but the last one, which the next tile of the run takes (or the seam pass
   // at the end of a run), unless the frame ends there; column 0 of a run
   // with another run to its left is a seam.  Window columns l - 1, l, l + 1
@@ -2364,7 +2377,7 @@ __device__ __attribute__((always_inline)) inline void fused_tile(
     const int cm = x0 + lane == 0 ? 0 : lane - 1;
     const int cp = x0 + lane + 1 == a.W ? lane : lane + 1;
     const float* base = &coef[0][0][0];
-    const int r0 = kFusedRows * wave, r1 = min(r0 + kFusedRows, h);
+    const int r0 = kRows * wave, r1 = min(r0 + kRows, h);
     auto load_row = [&](int r, float (&wv)[3][3]) {
       const float* rp = base + rowidx(r) * kRecLd;
 #pragma unroll
@@ -2433,12 +2446,14 @@ __device__ __attribute__((always_inline)) inline void fused_unit(const FusedArgs
     recon_core<SPLIT>(f.rec, tx, ty, q, [&](float (*coef)[kRecTH][kRecLd], const int* s_bad) {
       const bool first = tx == tx0, last = tx + 1 == tx1;
       if (fmt == JXLR_OUT_F32)
-        fused_tile<JXLR_OUT_F32>(f, coef, s_bad, carry, tx, ty, first, last, nullptr, nullptr);
+        fused_tile<JXLR_OUT_F32, kRecThreads>(f, coef, s_bad, carry, tx, ty, first, last,
+                                              nullptr, nullptr);
       else if (fmt == JXLR_OUT_U8_SRGB)
-        fused_tile<JXLR_OUT_U8_SRGB>(f, coef, s_bad, carry, tx, ty, first, last, s_thr, start8);
+        fused_tile<JXLR_OUT_U8_SRGB, kRecThreads>(f, coef, s_bad, carry, tx, ty, first, last,
+                                                  s_thr, start8);
       else
-        fused_tile<JXLR_OUT_U16_SRGB>(f, coef, s_bad, carry, tx, ty, first, last, f.fin.thr,
-                                      nullptr);
+        fused_tile<JXLR_OUT_U16_SRGB, kRecThreads>(f, coef, s_bad, carry, tx, ty, first, last,
+                                                   f.fin.thr, nullptr);
     });
   }
 }
@@ -2573,131 +2588,58 @@ __device__ __attribute__((always_inline)) inline void seam_unit(const FusedArgs&
 // the EPF passes and the finish (no quantization constraint, patches, dots,
 // splines or noise), the last pass's output need not pass through HBM: the
 // EPF workgroup writes its filtered tile into LDS (over its staging cells,
-// which stage E no longer reads), finishes there the pixels whose Gaborish
-// window lies in the tile, and writes the samples along each side that
-// faces another tile into the tile's seam record; the seam pass (runs of
-// one tile) finishes the rest.  Every pixel goes through the finish's
+// which stage E no longer reads) and finishes it there with fused_tile, as
+// a run of one tile of the fused reconstruction (seams at every tile
+// boundary, the seam pass after).  Every pixel goes through the finish's
 // operations in the same order, so the output equals that of the pass
-// followed by the finish bit for bit.
+// followed by the finish bit for bit.  (Runs of several tiles per
+// workgroup, as the reconstruction has, measured slower here: two resident
+// workgroups per CU leave too little overlap for tiles taken in turn.)
 struct EpfFinish {
   FinishArgs fin;
   float* seam;  // kSeamTileF floats per tile, tiles in row order
   int tiles_x, tiles_y;
 };
 
-// Rows of a tile per wave in the EPF-fused finish (eight waves).
-constexpr int kEpfFinRows = kRecTH / (kEpfThreads / 64);
-static_assert(kEpfFinRows == 4, "EPF tile rows per wave");
-static_assert(sizeof(float) * 3 * kRecTH * kRecLd <= sizeof(uint4) * kQH * kQW,
+static_assert(sizeof(float) * (4 + 3 * kRecTH * kRecLd) <= sizeof(uint4) * kQH * kQW,
               "the filtered tile fits over the staging cells");
 static_assert(sizeof(float) * 257 + kSrgbBucketsPadded <= sizeof(uint32_t) * 3 * kQH * (kGW + 1),
               "the 8-bit code tables fit over the guide words");
-
-template <int FMT>
-__device__ __attribute__((always_inline)) inline void epf_finish_tile(
-    const EpfFinish& e, float (*tile)[kRecTH][kRecLd], int tx, int ty,
-    const float* __restrict__ thr, const uint8_t* __restrict__ start8) {
-  using T = typename OutT<FMT>::T;
-  const FinishArgs& a = e.fin;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int x0 = kRecTW * tx, y0 = kRecTH * ty;
-  const int w = min(kRecTW, a.W - x0), h = min(kRecTH, a.H - y0);
-  const bool up = ty > 0, down = ty + 1 < e.tiles_y;
-  const bool left = tx > 0, right = tx + 1 < e.tiles_x;
-  float* rec = e.seam + (size_t(ty) * e.tiles_x + tx) * kSeamTileF;
-  // seam records: waves 0-3 the row records (lane = column), waves 4-5 the
-  // column records (thread = record, row)
-  if (wave < 4) {
-    const int r = wave, y = r < 2 ? r : h - 4 + r;
-    if ((r < 2 ? up : down) && lane < w && y >= 0 && y < h) {
-#pragma unroll
-      for (int c = 0; c < 3; ++c) rec[r * kSeamRowF + c * kRecTW + lane] = tile[c][y][lane];
-    }
-  } else if (wave < 6) {
-    const int i = tid - 256, q = i >> 5, y = i & 31;
-    const int x = q < 2 ? q : w - 4 + q;
-    if ((q < 2 ? left : right) && y < h && x >= 0 && x < w) {
-#pragma unroll
-      for (int c = 0; c < 3; ++c) rec[4 * kSeamRowF + q * kSeamColF + c * kRecTH + y] = tile[c][y][x];
-    }
-  }
-  // lane l takes column x0 + l of rows 4 wave ..: every column but the
-  // first (last) when a tile lies to the left (right), which are seams;
-  // window columns mirrored at the frame's edges
-  const bool col = lane < w && !(lane == 0 && left) && !(lane == w - 1 && right);
-  const int cm = min(max(mirror(x0 + lane - 1, a.W) - x0, 0), kRecTW - 1);
-  const int cp = min(max(mirror(x0 + lane + 1, a.W) - x0, 0), kRecTW - 1);
-  auto rowidx = [&](int r) { return min(max(mirror(y0 + r, a.H) - y0, 0), h - 1); };
-  auto load_row = [&](int r, float (&wv)[3][3]) {
-    const int yy = rowidx(r);
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      wv[c][0] = tile[c][yy][cm];
-      wv[c][1] = tile[c][yy][lane];
-      wv[c][2] = tile[c][yy][cp];
-    }
-  };
-  T* out[3] = {static_cast<T*>(a.out[0]), static_cast<T*>(a.out[1]), static_cast<T*>(a.out[2])};
-  const int r0 = kEpfFinRows * wave;
-  float wv[3][3][3];
-  load_row(r0 - 1, wv[0]);
-  load_row(r0, wv[1]);
-#pragma unroll
-  for (int i = 0; i < kEpfFinRows; ++i) {
-    const int r = r0 + i, u = i % 3, m = (i + 1) % 3, d = (i + 2) % 3;
-    load_row(r + 1, wv[d]);
-    if (col && r < h && !((r == 0 && up) || (r == h - 1 && down))) {
-      float v[3];
-      if (a.gab) {
-        gab_pixel(a, wv[u], wv[m], wv[d], v);
-      } else {
-#pragma unroll
-        for (int c = 0; c < 3; ++c) v[c] = wv[m][c][1];
-      }
-      float rgb[3];
-      xyb_to_rgb(a, v, rgb);
-      const size_t o = size_t(y0 + r) * a.out_stride + x0 + lane;
-#pragma unroll
-      for (int c = 0; c < 3; ++c) out[c][o] = encode_out<FMT>(rgb[c], thr, start8);
-    }
-  }
-}
 
 // epf_core's epilogue with the finish fused (EpfFinish e) for tile (tx, ty).
 __device__ __attribute__((always_inline)) inline void epf_fin_epilogue(
     const EpfFinish& e, int tx, int ty, const float (&res)[kEpfRows][3], int nrows, uint4* sq,
     uint32_t* sw) {
-    const int tid = threadIdx.x, lx = tid & 63, row0 = kEpfRows * (tid >> 6);
-    float (*tile)[kRecTH][kRecLd] = reinterpret_cast<float (*)[kRecTH][kRecLd]>(sq);
-    float* s_thr = reinterpret_cast<float*>(sw);
-    uint8_t* s_start = reinterpret_cast<uint8_t*>(sw + 257);
-    const int fmt = e.fin.format;
-    __syncthreads();  // stage E's reads of the staging cells are done
+  const int tid = threadIdx.x, lx = tid & 63, row0 = kEpfRows * (tid >> 6);
+  // the tile in the reconstruction's layout, 16 bytes into the staging
+  // cells (as in recon_core)
+  float (*tile)[kRecTH][kRecLd] =
+      reinterpret_cast<float (*)[kRecTH][kRecLd]>(reinterpret_cast<float*>(sq) + 4);
+  float* s_thr = reinterpret_cast<float*>(sw);
+  uint8_t* s_start = reinterpret_cast<uint8_t*>(sw + 257);
+  const int fmt = e.fin.format;
+  __syncthreads();  // stage E's reads of the staging cells are done
 #pragma unroll
-    for (int i = 0; i < kEpfRows; ++i)
-      if (i < nrows)
+  for (int i = 0; i < kEpfRows; ++i)
+    if (i < nrows)
 #pragma unroll
-        for (int c = 0; c < 3; ++c) tile[c][row0 + i][lx] = res[i][c];
-    if (fmt == JXLR_OUT_U8_SRGB) {
-      for (int i = tid; i < 257; i += kEpfThreads) s_thr[i] = e.fin.thr[i];
-      for (int i = tid; i < kSrgbBucketsPadded / 4; i += kEpfThreads)
-        reinterpret_cast<uint32_t*>(s_start)[i] = reinterpret_cast<const uint32_t*>(e.fin.start8)[i];
-    }
-    __syncthreads();
-    if (fmt == JXLR_OUT_F32)
-      epf_finish_tile<JXLR_OUT_F32>(e, tile, tx, ty, nullptr, nullptr);
-    else if (fmt == JXLR_OUT_U8_SRGB)
-      epf_finish_tile<JXLR_OUT_U8_SRGB>(e, tile, tx, ty, s_thr, s_start);
-    else
-      epf_finish_tile<JXLR_OUT_U16_SRGB>(e, tile, tx, ty, e.fin.thr, nullptr);
-}
-
-// The EPF pass of tile (tx, ty) with the finish fused.
-__device__ __attribute__((always_inline)) inline void epf_fin_tile(const EpfArgs& a,
-                                                                   const EpfFinish& e, int tx,
-                                                                   int ty) {
-  epf_core(a, tx, ty, [&](const float (&res)[kEpfRows][3], int, int, int nrows, uint4* sq,
-                          uint32_t* sw) { epf_fin_epilogue(e, tx, ty, res, nrows, sq, sw); });
+      for (int c = 0; c < 3; ++c) tile[c][row0 + i][lx] = res[i][c];
+  if (fmt == JXLR_OUT_U8_SRGB) {
+    for (int i = tid; i < 257; i += kEpfThreads) s_thr[i] = e.fin.thr[i];
+    for (int i = tid; i < kSrgbBucketsPadded / 4; i += kEpfThreads)
+      reinterpret_cast<uint32_t*>(s_start)[i] = reinterpret_cast<const uint32_t*>(e.fin.start8)[i];
+  }
+  __syncthreads();
+  // a run of one tile: no carried columns
+  if (fmt == JXLR_OUT_F32)
+    fused_tile<JXLR_OUT_F32, kEpfThreads>(e, tile, nullptr, nullptr, tx, ty, true, true, nullptr,
+                                          nullptr);
+  else if (fmt == JXLR_OUT_U8_SRGB)
+    fused_tile<JXLR_OUT_U8_SRGB, kEpfThreads>(e, tile, nullptr, nullptr, tx, ty, true, true, s_thr,
+                                              s_start);
+  else
+    fused_tile<JXLR_OUT_U16_SRGB, kEpfThreads>(e, tile, nullptr, nullptr, tx, ty, true, true,
+                                               e.fin.thr, nullptr);
 }
 
 // ---------------------------------------------------------------------------
@@ -3397,14 +3339,16 @@ __global__ __launch_bounds__(kRecThreads, 4) void qco_kernel(QcoArgs a, int tile
   const int t = xcd_tile(blockIdx.x, gridDim.x);
   qco_tile(a, t % tiles_x, t / tiles_x);
 }
-__global__ __launch_bounds__(kEpfThreads, kEpfMinBlocks) void epf_kernel(EpfArgs a, int tiles_x) {
+__global__ __launch_bounds__(kEpfThreads, kEpfWavesPerSimd) void epf_kernel(EpfArgs a, int tiles_x) {
   const int t = xcd_tile(blockIdx.x, gridDim.x);
   epf_tile(a, t % tiles_x, t / tiles_x);
 }
-__global__ __launch_bounds__(kEpfThreads, kEpfMinBlocks) void epf_fin_kernel(EpfArgs a,
+__global__ __launch_bounds__(kEpfThreads, kEpfWavesPerSimd) void epf_fin_kernel(EpfArgs a,
                                                                              EpfFinish e) {
   const int t = xcd_tile(blockIdx.x, gridDim.x);
-  epf_fin_tile(a, e, t % e.tiles_x, t / e.tiles_x);
+  const int tx = t % e.tiles_x, ty = t / e.tiles_x;
+  epf_core(a, tx, ty, [&](const float (&res)[kEpfRows][3], int, int, int nrows, uint4* sq,
+                          uint32_t* sw) { epf_fin_epilogue(e, tx, ty, res, nrows, sq, sw); });
 }
 template <bool NOISE>
 __global__ __launch_bounds__(fin_threads<kFinRowsFrame>()) void finish_kernel(FinishArgs a,
@@ -3524,7 +3468,7 @@ __global__ __launch_bounds__(kRecThreads) void recon_batch_kernel(BatchArgs b) {
 }
 
 template <bool PERSIST>
-__global__ __launch_bounds__(kEpfThreads, kEpfMinBlocks) void epf_batch_kernel(BatchArgs b) {
+__global__ __launch_bounds__(kEpfThreads, kEpfWavesPerSimd) void epf_batch_kernel(BatchArgs b) {
   for (TileRange r(b.order, b.tile_start[b.n]); r.t < r.end; r.t += r.step) {
     if (PERSIST) __syncthreads();
     const int f = __builtin_amdgcn_readfirstlane(b.tile_frame[r.t]);
