@@ -42,11 +42,16 @@ HBM_PEAK_GBS = 8000.0
 # lane), which the integer SAD, compare and select ops cannot use and which
 # the build disables.
 ALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
-# Algorithmic work per pixel of one EPF pass (separable formulation): for each
-# of the 56 window offsets, one packed 3-channel SAD of the new sample pair,
-# 3 + 2 adds of the 4x3 patch box sum, 6 ops of Weight and the threshold,
-# 4 FMAs of the weighted sums (3 channels and the weight total).
-EPF_OPS_PER_PX = 56 * (1 + 5 + 7 + 4)
+# Algorithmic work per pixel of one EPF pass, in 32-bit lane operations of
+# the formulation the kernel uses (an operation = one VALU instruction of
+# one lane; the bound is VALU issue): for each of the 56 window offsets,
+# 4.5 packed-byte SADs (the 3 channels x 6 guide rows of a 4-row strip, 4
+# columns a byte each, shared by the strip's 4 pixels), one three-input add
+# of the patch sum, one multiply-add indexing the weight table, a compare
+# and a select for the weight threshold, one add of the weight total and 3
+# FMAs of the weighted channel sums.  Staging, guide bytes, ranges, sigma
+# and the normalization are not counted.
+EPF_OPS_PER_PX = int(56 * (4.5 + 1 + 1 + 2 + 1 + 3))
 # Algorithmic HBM bytes per pixel of the other kernels: int32 AC in, f32 XYB
 # out for reconstruct; f32 XYB in, f32 / u8 / u16 RGB out for finish.
 RECON_BYTES_PER_PX = 12 + 12
