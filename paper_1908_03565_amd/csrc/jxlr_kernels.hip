@@ -2437,14 +2437,23 @@ __device__ __attribute__((always_inline)) inline void fused_unit(const FusedArgs
   const uint8_t* start8 = reinterpret_cast<const uint8_t*>(s_start);
   const int ty = u / f.runs_x, tx0 = (u - ty * f.runs_x) * f.run;
   const int tx1 = min(tx0 + f.run, f.tiles_x);
-  for (int tx = tx0; tx < tx1; ++tx) {
-    if (tx > tx0) __syncthreads();  // the previous tile's reads of LDS are done
+  // the AC of the run's next tile is loaded while this one is finished (the
+  // registers are free once the dequantization has read them)
+  int4 q[kRecGPT][3];
+  {
     int tid = threadIdx.x;  // opaque, as in recon_core
     asm volatile("" : "+v"(tid));
-    int4 q[kRecGPT][3];
-    recon_load_ac(f.rec, tx, ty, tid, q);
+    recon_load_ac(f.rec, tx0, ty, tid, q);
+  }
+  for (int tx = tx0; tx < tx1; ++tx) {
+    if (tx > tx0) __syncthreads();  // the previous tile's reads of LDS are done
     recon_core<SPLIT>(f.rec, tx, ty, q, [&](float (*coef)[kRecTH][kRecLd], const int* s_bad) {
       const bool first = tx == tx0, last = tx + 1 == tx1;
+      if (!last) {
+        int tid = threadIdx.x;
+        asm volatile("" : "+v"(tid));
+        recon_load_ac(f.rec, tx + 1, ty, tid, q);
+      }
       if (fmt == JXLR_OUT_F32)
         fused_tile<JXLR_OUT_F32, kRecThreads>(f, coef, s_bad, carry, tx, ty, first, last,
                                               nullptr, nullptr);
