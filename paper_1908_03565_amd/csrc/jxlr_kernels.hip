@@ -2330,8 +2330,9 @@ __device__ __attribute__((always_inline)) inline void fused_tile(
   }
 
   T* out[3] = {static_cast<T*>(a.out[0]), static_cast<T*>(a.out[1]), static_cast<T*>(a.out[2])};
+  // zero: store 0 in place of the pixel (a seam column, see below)
   auto finish_px = [&](int x, int r, const float (&u)[3][3], const float (&m)[3][3],
-                       const float (&d)[3][3]) {
+                       const float (&d)[3][3], bool zero = false) {
     float v[3];
     if (a.gab) {
       gab_pixel(a, u, m, d, v);
@@ -2343,7 +2344,7 @@ __device__ __attribute__((always_inline)) inline void fused_tile(
     xyb_to_rgb(a, v, rgb);
     const size_t o = size_t(y0 + r) * a.out_stride + x;
 #pragma unroll
-    for (int c = 0; c < 3; ++c) out[c][o] = encode_out<FMT>(rgb[c], thr, start8);
+    for (int c = 0; c < 3; ++c) out[c][o] = zero ? T(0) : encode_out<FMT>(rgb[c], thr, start8);
   };
   auto rowidx = [&](int r) { return min(max(mirror(y0 + r, a.H) - y0, 0), h - 1); };
   auto seam_row = [&](int r) { return (r == 0 && up) || (r == h - 1 && down); };
@@ -2371,9 +2372,14 @@ __device__ __attribute__((always_inline)) inline void fused_tile(
   // at the end of a run), unless the frame ends there; column 0 of a run
   // with another run to its left is a seam.  Window columns l - 1, l, l + 1
   // (mirrored at the frame's edges; -1: the tile before's last column, kept
-  // in coef's column -1), read at uniform strides.
+  // in coef's column -1), read at uniform strides.  The lanes of the
+  // columns the seam pass finishes store a 0 there, which it overwrites
+  // later: a wave's row store then covers whole cache lines, where a store
+  // with a gap makes the cache fetch the line from HBM to merge it (the
+  // 8-bit rows of the 64-frame batch fetched twice the filter's input).
   {
     const bool col = (lane == 0 && left) ? false : lane < w - 1 ? true : (lane == w - 1 && frame_end);
+    const bool seam_col = (lane == 0 && left) || (lane == w - 1 && right);
     const int cm = x0 + lane == 0 ? 0 : lane - 1;
     const int cp = x0 + lane + 1 == a.W ? lane : lane + 1;
     const float* base = &coef[0][0][0];
@@ -2392,16 +2398,17 @@ __device__ __attribute__((always_inline)) inline void fused_tile(
     float wa[3][3], wb[3][3], wc[3][3];
     load_row(r0 - 1, wa);
     load_row(r0, wb);
+    const bool st = col || seam_col;
 #pragma unroll 1
     for (int r = r0; r < r1; r += 3) {
       load_row(r + 1, wc);
-      if (col && !seam_row(r)) finish_px(x0 + lane, r, wa, wb, wc);
+      if (st && !seam_row(r)) finish_px(x0 + lane, r, wa, wb, wc, seam_col);
       if (r + 1 >= r1) break;
       load_row(r + 2, wa);
-      if (col && !seam_row(r + 1)) finish_px(x0 + lane, r + 1, wb, wc, wa);
+      if (st && !seam_row(r + 1)) finish_px(x0 + lane, r + 1, wb, wc, wa, seam_col);
       if (r + 2 >= r1) break;
       load_row(r + 3, wb);
-      if (col && !seam_row(r + 2)) finish_px(x0 + lane, r + 2, wc, wa, wb);
+      if (st && !seam_row(r + 2)) finish_px(x0 + lane, r + 2, wc, wa, wb, seam_col);
     }
   }
 
