@@ -328,7 +328,8 @@ def bench_frame(args, J, wl, torch, np):
              + ("_noise" if nz else "") + (f"_patches{args.patches}" if args.patches else "")
              + (f"_dots{args.dots}" if args.dots else "")
              + (f"_splines{args.splines}" if args.splines else ""))
-    roofline = roofline_of(kernels, {"epf_kernel": n_plain}, wname, W * H)
+    roofline = roofline_of(kernels, {"epf_kernel": n_plain},
+                           wname + ("_nofuse" if args.no_fuse else ""), W * H)
 
     graph_lat = None
     if args.workload == "c1":
@@ -552,7 +553,10 @@ def bench_batch(args, J, wl, torch, np):
         kernels["fused_batch_kernel"] = dict(
             ms=sms["fused"], bound="hbm", bytes_per_px=fb,
             achieved=fused_px * fb / (sms["fused"] / 1e3) / 1e9)
-    roofline = roofline_of(kernels, {"epf_batch_kernel": n_epf}, name, px)
+    # the counters were taken on the default form (finish fused where it
+    # can be); the stages apart move other bytes
+    roofline = roofline_of(kernels, {"epf_batch_kernel": n_epf},
+                           name + ("_nofuse" if args.no_fuse else ""), px)
     # the whole step against the algorithmic bytes of the path (coefficients
     # in, output out; maps and DC add under 0.3 B/px)
     e2e_bpp = FUSED_BYTES_PER_PX[fmt]
