@@ -2414,7 +2414,7 @@ __device__ __attribute__((always_inline)) inline void fused_tile(
       const float v62 = coef[c][y][kRecTW - 2], v63 = coef[c][y][kRecTW - 1];
       carry[c][y][0] = v62;
       carry[c][y][1] = v63;
-      coef[c][y][-1] = v63;
+      (&coef[c][y][0])[-1] = v63;  // row y's column -1, inside coef_mem
     }
   }
 }
@@ -3624,16 +3624,20 @@ __global__ __launch_bounds__(kSplineThreads) void spline_batch_kernel(OptBatch o
 }
 
 // Reconstruction fused with the finish, and the seam pass after it: one
-// workgroup per run of tiles (FusedArgs); single-frame and batch forms.
+// workgroup per run of tiles (FusedArgs); single-frame and batch forms.  The
+// next tile's coefficients held through the finish take the registers to
+// about 160, three waves per SIMD (capping them at 128 spills and runs
+// slower).
+constexpr int kFusedWavesPerSimd = 3;
 template <bool SPLIT>
-__global__ __launch_bounds__(kRecThreads, kRecMinBlocks) void fused_kernel(FusedArgs f) {
+__global__ __launch_bounds__(kRecThreads, kFusedWavesPerSimd) void fused_kernel(FusedArgs f) {
   fused_unit<SPLIT>(f, xcd_tile(blockIdx.x, gridDim.x));
 }
 __global__ __launch_bounds__(kSeamThreads) void seam_kernel(FusedArgs f) {
   seam_unit(f, blockIdx.x);
 }
 template <bool SPLIT>
-__global__ __launch_bounds__(kRecThreads, kRecMinBlocks) void fused_batch_kernel(OptBatch ob) {
+__global__ __launch_bounds__(kRecThreads, kFusedWavesPerSimd) void fused_batch_kernel(OptBatch ob) {
   __shared__ FusedArgs s_args;
   int row;
   const int u = opt_unit_lds(ob, s_args, row);
@@ -4192,9 +4196,11 @@ jxlr_status make_finish_args(jxlr_ctx* ctx, const jxlr_frame_params* p, const jx
 }
 
 // Tiles per run of the fused path: longer runs (fewer seams) while the
-// units still fill the device about twice over.
+// units still fill the device about twice over (at the workgroups per CU
+// the launch bound allows).
 int fused_run_length(const jxlr_ctx* ctx, long long tiles) {
-  const long long fill = 2LL * std::max(ctx->cus, 1) * kRecMinBlocks;
+  constexpr int per_cu = kFusedWavesPerSimd * 4 * 64 / kRecThreads;
+  const long long fill = 2LL * std::max(ctx->cus, 1) * per_cu;
   return int(std::max(1LL, std::min<long long>(kRunMax, tiles / fill)));
 }
 
