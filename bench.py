@@ -80,29 +80,29 @@ def log(msg):
 PMC_COPY_SCALE = {"FETCH_SIZE": 2.0, "WRITE_SIZE": 1.0}
 PMC_SOURCES = ("paper_1908_03565_amd/csrc/jxlr_kernels.hip", "paper_1908_03565_amd/csrc/jxlr_tables.cpp",
                "paper_1908_03565_amd/csrc/jxlr_tables.h", "paper_1908_03565_amd/csrc/gen_dct_consts.py")
-PMC_SOURCES_SHA256 = "a1f4b31772ff211bd0b6985c41c453f23cba9d5da05e69de9861eb6dac2b10db"
+PMC_SOURCES_SHA256 = "193068e21e32f07bcab632ff114454102ca3d976de924cfb49407adb1a2081a8"
 # (workload name, kernel) -> (FETCH_SIZE KiB, WRITE_SIZE KiB) per dispatch
 PMC_KIB = {
-    ("c4_batch64_loguniform_256_3072_epf1_u8srgb", "recon_batch_kernel"): (536142.6, 1060148.0),
-    ("c4_batch64_loguniform_256_3072_epf1_u8srgb", "epf_batch_kernel"): (528763.1, 440193.4),
-    ("c4_batch64_loguniform_256_3072_epf1_u8srgb", "seam_batch_kernel"): (112264.7, 190731.1),
+    ("c4_batch64_loguniform_256_3072_epf1_u8srgb", "recon_batch_kernel"): (536135.7, 1059857.1),
+    ("c4_batch64_loguniform_256_3072_epf1_u8srgb", "epf_batch_kernel"): (528763.2, 440192.2),
+    ("c4_batch64_loguniform_256_3072_epf1_u8srgb", "seam_batch_kernel"): (112268.5, 190793.8),
     ("c4_batch64_loguniform_256_3072_epf1_u8srgb", "finish_batch_kernel"): (122.7, 0.0),
-    ("c1x1024_256x256_dct8", "fused_batch_kernel"): (432031.9, 927757.8),
+    ("c1x1024_256x256_dct8", "fused_batch_kernel"): (432847.7, 927319.6),
     ("c1x1024_256x256_dct8", "seam_batch_kernel"): (45260.7, 43008.0),
-    ("c2_2048x2048_mixed_epf2", "recon_kernel"): (25482.5, 49152.0),
-    ("c2_2048x2048_mixed_epf2", "epf_kernel"): (25449.0, 49152.0),
-    ("c2_2048x2048_mixed_epf2", "epf_fin_kernel"): (25480.6, 55152.0),
-    ("c2_2048x2048_mixed_epf2", "seam_kernel"): (5226.1, 14195.6),
-    ("c3_4096x4096_half_dct32", "recon_kernel"): (100677.3, 196612.4),
-    ("c3_4096x4096_half_dct32", "epf_kernel"): (101080.6, 196608.0),
-    ("c3_4096x4096_half_dct32", "epf_fin_kernel"): (100292.5, 220896.0),
-    ("c3_4096x4096_half_dct32", "seam_kernel"): (23145.1, 57575.6),
+    ("c2_2048x2048_mixed_epf2", "recon_kernel"): (25483.7, 49152.4),
+    ("c2_2048x2048_mixed_epf2", "epf_kernel"): (25449.1, 49152.0),
+    ("c2_2048x2048_mixed_epf2", "epf_fin_kernel"): (25480.5, 55152.0),
+    ("c2_2048x2048_mixed_epf2", "seam_kernel"): (5225.8, 14195.6),
+    ("c3_4096x4096_half_dct32", "recon_kernel"): (100682.0, 196631.7),
+    ("c3_4096x4096_half_dct32", "epf_kernel"): (101067.3, 196608.0),
+    ("c3_4096x4096_half_dct32", "epf_fin_kernel"): (102579.2, 220896.0),
+    ("c3_4096x4096_half_dct32", "seam_kernel"): (23210.3, 57575.6),
     ("j1_jpeg1_4096x4096_420", "jpeg1_idct_kernel"): (16411.1, 32768.0),
-    ("j1_jpeg1_4096x4096_420", "jpeg1_color_kernel"): (81882.4, 196608.0),
-    ("c2_2048x2048_mixed_epf2_qco", "recon_kernel"): (25482.5, 49152.4),
+    ("j1_jpeg1_4096x4096_420", "jpeg1_color_kernel"): (82024.2, 196608.0),
+    ("c2_2048x2048_mixed_epf2_qco", "recon_kernel"): (25483.0, 49152.0),
     ("c2_2048x2048_mixed_epf2_qco", "epf_kernel"): (25449.0, 49152.0),
-    ("c2_2048x2048_mixed_epf2_qco", "qco_kernel"): (70892.5, 49152.0),
-    ("c2_2048x2048_mixed_epf2_qco", "finish_kernel"): (24952.7, 49152.0),
+    ("c2_2048x2048_mixed_epf2_qco", "qco_kernel"): (70960.7, 49152.0),
+    ("c2_2048x2048_mixed_epf2_qco", "finish_kernel"): (24882.5, 49152.0),
 }
 
 
