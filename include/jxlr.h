@@ -474,11 +474,15 @@ jxlr_status jxlr_epf_finish(jxlr_ctx* ctx, const jxlr_frame_params* p, const jxl
  * JXLR_E_WORKSPACE for a seam buffer below jxlr_seam_bytes(p), and those of
  * jxlr_reconstruct and jxlr_finish.  jxlr_decode takes this path for every
  * frame that qualifies. */
-/* 0 for a frame that qualifies for neither fused path */
-size_t jxlr_seam_bytes(const jxlr_frame_params* p);
 jxlr_status jxlr_reconstruct_finish(jxlr_ctx* ctx, const jxlr_frame_params* p,
                                     const jxlr_frame_io* io, const uint8_t* info, float* seam,
                                     size_t seam_bytes, hipStream_t stream);
+
+/* Bytes of the seam buffer that jxlr_epf_finish and jxlr_reconstruct_finish
+ * take for frame p: the samples of each 64x32 tile's outer two rows and
+ * columns in all three channels (4.5 KiB per tile), rounded up to 256 bytes;
+ * 0 for a frame that qualifies for neither fused path. */
+size_t jxlr_seam_bytes(const jxlr_frame_params* p);
 
 /* ---- JPEG1 direct rasterization (M.6) ----------------------------------------
  * A recompressed JPEG1 frame (M.4 already decoded: quantized DCT coefficients
