@@ -122,8 +122,11 @@ def traffic_bytes(workload, kernel):
     return int(round(1024 * (kib[0] * PMC_COPY_SCALE["FETCH_SIZE"] + kib[1] * PMC_COPY_SCALE["WRITE_SIZE"])))
 
 
-def roofline_of(kernels, weights, workload=None, px=None):
-    """kernels: name -> dict(ms, bound, achieved); weights: launches per step."""
+def roofline_of(kernels, weights, workload=None, px=None, alu_bytes_per_px=24):
+    """kernels: name -> dict(ms, bound, achieved); weights: launches per step;
+    alu_bytes_per_px: HBM bytes per pixel of an ALU-bound dominant kernel
+    (an EPF pass: 12 in + 12 out, or 12 in + the output format's bytes when
+    the finish is fused into it)."""
     dominant = max(kernels, key=lambda k: kernels[k]["ms"] * weights.get(k, 1))
     dk = kernels[dominant]
     traffic = traffic_bytes(workload, dominant)
@@ -132,7 +135,7 @@ def roofline_of(kernels, weights, workload=None, px=None):
                     peak=round(ALU_PEAK_TOPS, 3), unit="Top/s",
                     frac=round(dk["achieved"] / ALU_PEAK_TOPS, 4), avg_ms=round(dk["ms"], 5),
                     ops_per_px=EPF_OPS_PER_PX, traffic=traffic,
-                    algorithmic_bytes=24 * px if px else None)
+                    algorithmic_bytes=alu_bytes_per_px * px if px else None)
     return dict(bound="hbm", kernel=dominant, achieved=round(dk["achieved"], 1), peak=HBM_PEAK_GBS,
                 unit="GB/s", frac=round(dk["achieved"] / HBM_PEAK_GBS, 4),
                 avg_ms=round(dk["ms"], 5), bytes_per_px=dk.get("bytes_per_px"), traffic=traffic,
@@ -555,8 +558,11 @@ def bench_batch(args, J, wl, torch, np):
             achieved=fused_px * fb / (sms["fused"] / 1e3) / 1e9)
     # the counters were taken on the default form (finish fused where it
     # can be); the stages apart move other bytes
+    # every pass but a frame's last reads and writes binary32 XYB; the last
+    # writes the output instead where the finish is fused into it
+    alu_b = 24 if n_epf > 1 or epf_fin_px < tile_px else FUSED_BYTES_PER_PX[fmt]
     roofline = roofline_of(kernels, {"epf_batch_kernel": n_epf},
-                           name + ("_nofuse" if args.no_fuse else ""), px)
+                           name + ("_nofuse" if args.no_fuse else ""), px, alu_b)
     # the whole step against the algorithmic bytes of the path (coefficients
     # in, output out; maps and DC add under 0.3 B/px)
     e2e_bpp = FUSED_BYTES_PER_PX[fmt]
